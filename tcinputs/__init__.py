@@ -1,0 +1,252 @@
+"""Seeded synthetic inputs shared by the oracle, the tests and the benchmark.
+
+This module holds geometry and random-number plumbing only: lattice vectors,
+Gamma-centred Monkhorst-Pack k lists, plane-wave index sets inside a kinetic
+cutoff, random orbital coefficients and occupations.  It contains none of the
+transcorrelated method's arithmetic (no kernels, no transforms, no terms), so
+that both the CPU oracle and the HIP library can consume the same inputs
+without sharing any of the computation they are compared on.
+
+Conventions (also used by the C ABI):
+  * lattice rows are a1, a2, a3 in bohr; reciprocal rows b_j satisfy
+    a_i . b_j = 2 pi delta_ij;
+  * k-points are Gamma-centred: k = (i1/n1, i2/n2, i3/n3) in units of b, with
+    flat index ik = (i1*n2 + i2)*n3 + i3 (fractions kept in [0, 1));
+  * an orbital's coefficients c(G) over Miller indices m give the cell-periodic
+    part phi(r) = Omega^{-1/2} sum_G c(G) exp(i G.r), sum |c|^2 = 1.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import List, Optional
+
+import numpy as np
+
+SEED_BASE = 230207420
+
+
+def sc_lattice(L: float) -> np.ndarray:
+    return np.eye(3) * float(L)
+
+
+def fcc_lattice(a: float) -> np.ndarray:
+    h = 0.5 * float(a)
+    return np.array([[0.0, h, h], [h, 0.0, h], [h, h, 0.0]])
+
+
+def reciprocal(lattice: np.ndarray) -> np.ndarray:
+    return 2.0 * math.pi * np.linalg.inv(np.asarray(lattice, dtype=np.float64)).T
+
+
+def kmesh_fractions(n1: int, n2: int, n3: int) -> np.ndarray:
+    out = []
+    for i1 in range(n1):
+        for i2 in range(n2):
+            for i3 in range(n3):
+                out.append((i1 / n1, i2 / n2, i3 / n3))
+    return np.array(out, dtype=np.float64)
+
+
+def miller_sphere(lattice: np.ndarray, kfrac, ecut: float) -> np.ndarray:
+    """Miller indices m with |k+G|^2/2 <= ecut, sorted by (|k+G|^2, m)."""
+    B = reciprocal(lattice)
+    kc = math.sqrt(2.0 * ecut)
+    bmin = min(np.linalg.norm(B, axis=1))
+    # bound on |m_i| from the dual basis
+    mmax = int(math.ceil(kc * np.max(np.linalg.norm(np.asarray(lattice), axis=1)) / (2 * math.pi))) + 2
+    r = np.arange(-mmax, mmax + 1)
+    M = np.stack(np.meshgrid(r, r, r, indexing="ij"), -1).reshape(-1, 3)
+    kg = (M + np.asarray(kfrac)[None, :]) @ B
+    e = 0.5 * np.sum(kg * kg, axis=1)
+    keep = e <= ecut + 1e-12
+    M, e = M[keep], e[keep]
+    order = np.lexsort((M[:, 2], M[:, 1], M[:, 0], np.round(e, 12)))
+    del bmin
+    return M[order].astype(np.int32)
+
+
+def miller_norm2(mmax2: int) -> np.ndarray:
+    """All integer vectors with |m|^2 <= mmax2 (simple cubic shells)."""
+    r = int(math.isqrt(mmax2)) + 1
+    rr = np.arange(-r, r + 1)
+    M = np.stack(np.meshgrid(rr, rr, rr, indexing="ij"), -1).reshape(-1, 3)
+    n2 = np.sum(M * M, axis=1)
+    M = M[n2 <= mmax2]
+    n2 = n2[n2 <= mmax2]
+    order = np.lexsort((M[:, 2], M[:, 1], M[:, 0], n2))
+    return M[order].astype(np.int32)
+
+
+@dataclasses.dataclass
+class Workload:
+    """One unpolarized synthetic problem (both spin channels identical)."""
+    name: str
+    lattice: np.ndarray            # (3,3) rows a_i
+    kmesh: tuple                   # (n1,n2,n3), Gamma-centred
+    grid: tuple                    # (N1,N2,N3)
+    miller: List[np.ndarray]       # per k: (npw,3) int32
+    right: List[np.ndarray]        # per k: (nb,npw) complex128
+    left: Optional[List[np.ndarray]]  # per k or None (TC mode)
+    occ: List[np.ndarray]          # per k: (nb,) fillings per spin-orbital
+    A: tuple                       # (A_par, A_anti)
+    C: tuple                       # (C_par, C_anti)
+    alpha: float                   # Gygi-Baldereschi auxiliary exponent
+    nelec_cell: int
+
+    @property
+    def omega(self) -> float:
+        return abs(float(np.linalg.det(self.lattice)))
+
+    @property
+    def nk(self) -> int:
+        return int(np.prod(self.kmesh))
+
+    @property
+    def kfrac(self) -> np.ndarray:
+        return kmesh_fractions(*self.kmesh)
+
+    @property
+    def nband(self) -> int:
+        return int(self.right[0].shape[0])
+
+    @property
+    def npairs(self) -> int:
+        """Same-spin (target, occupied partner) pairs for one spin channel."""
+        p = self.nk * self.nband
+        return p * p
+
+    def replace(self, **kw) -> "Workload":
+        return dataclasses.replace(self, **kw)
+
+
+def rpa_A(omega: float, nelec: int) -> float:
+    """RPA long-range amplitude sqrt(Omega / (4 pi N)) of the Jastrow function."""
+    return math.sqrt(omega / (4.0 * math.pi * nelec))
+
+
+def cusp_C(A: float):
+    """Parallel / antiparallel lengths from the approximate cusp condition."""
+    return (math.sqrt(2.0 * A), math.sqrt(A))
+
+
+def _orthonormal_random(rng, npw, nb, envelope):
+    z = rng.standard_normal((npw, nb)) + 1j * rng.standard_normal((npw, nb))
+    z *= envelope[:, None]
+    q, r = np.linalg.qr(z)
+    # fix the phase convention so that R has a positive diagonal
+    d = np.diag(r)
+    q = q * (d / np.abs(d))[None, :]
+    return np.ascontiguousarray(q.T)
+
+
+def random_orbitals(lattice, kmesh, ecut, nb, sigma, seed, left_mix=None):
+    B = reciprocal(lattice)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    mill, right, left = [], [], []
+    for kf in kmesh_fractions(*kmesh):
+        M = miller_sphere(lattice, kf, ecut)
+        G = M @ B
+        env = np.exp(-np.sum(G * G, axis=1) / (2.0 * sigma * sigma))
+        mill.append(M)
+        right.append(_orthonormal_random(rng, M.shape[0], nb, env))
+        if left_mix is not None:
+            z = rng.standard_normal((nb, M.shape[0])) + 1j * rng.standard_normal((nb, M.shape[0]))
+            z *= env[None, :]
+            z /= np.linalg.norm(z, axis=1, keepdims=True)
+            left.append(right[-1] + left_mix * z)
+    return mill, right, (left if left_mix is not None else None)
+
+
+def grid_fits(miller_list, grid) -> bool:
+    """True when every pair density is alias-free: N_i/2 >= 2 max|m_i| + 1."""
+    mx = np.max(np.stack([np.max(np.abs(m), axis=0) for m in miller_list]), axis=0)
+    return all(grid[i] // 2 >= 2 * mx[i] + 1 for i in range(3))
+
+
+# --------------------------------------------------------------------------
+# Named workloads.  Geometry follows the paper's examples (simple-cubic
+# electron gas; fcc diamond-lattice silicon cell a = 10.26 bohr); everything
+# else is synthetic.
+# --------------------------------------------------------------------------
+
+def heg_gamma(rs=4.0, nelec=14, grid=16, mmax2=9) -> Workload:
+    """Electron gas, 14 electrons, Gamma only: occupied shell |m|^2 <= 1."""
+    L = (nelec * 4.0 * math.pi / 3.0 * rs ** 3) ** (1.0 / 3.0)
+    lat = sc_lattice(L)
+    M = miller_norm2(mmax2)
+    occm = miller_norm2(1)                       # 7 plane waves
+    nb = occm.shape[0]
+    coef = np.zeros((nb, M.shape[0]), dtype=np.complex128)
+    for b, m in enumerate(occm):
+        idx = np.where(np.all(M == m[None, :], axis=1))[0][0]
+        coef[b, idx] = 1.0
+    A = rpa_A(L ** 3, nelec)
+    kc = 3.0 * 2.0 * math.pi / L
+    return Workload("heg14_gamma", lat, (1, 1, 1), (grid,) * 3, [M], [coef], None,
+                    [np.ones(nb)], (A, A), cusp_C(A), 10.0 / kc ** 2, nelec)
+
+
+def heg_twist(rs=2.0, nelec=54, tw=2, grid=32, ecut=None, nocc=27) -> Workload:
+    """Electron gas on a tw^3 twist grid; nocc lowest |k+G|^2 plane waves per twist."""
+    L = (nelec * 4.0 * math.pi / 3.0 * rs ** 3) ** (1.0 / 3.0)
+    lat = sc_lattice(L)
+    if ecut is None:
+        ecut = 5.78
+    mill, right = [], []
+    for kf in kmesh_fractions(tw, tw, tw):
+        M = miller_sphere(lat, kf, ecut)             # sorted by |k+G|^2 then m
+        coef = np.zeros((nocc, M.shape[0]), dtype=np.complex128)
+        coef[np.arange(nocc), np.arange(nocc)] = 1.0
+        mill.append(M)
+        right.append(coef)
+    A = rpa_A(L ** 3, nelec)
+    kc = math.sqrt(2.0 * ecut)
+    return Workload(f"heg{nelec}_twist{tw}", lat, (tw,) * 3, (grid,) * 3, mill, right, None,
+                    [np.ones(nocc) for _ in mill], (A, A), cusp_C(A), 10.0 / kc ** 2, nelec)
+
+
+def fcc_si(kmesh=(4, 4, 4), grid=24, ecut=8.14, nb=4, a=10.26, supercell=1,
+           seed_offset=2, left_mix=None, occ=None) -> Workload:
+    """Diamond-lattice silicon-like cell with random smooth orthonormal orbitals."""
+    lat = fcc_lattice(a) * supercell
+    nelec = 8 * supercell ** 3
+    omega = abs(np.linalg.det(lat))
+    sigma = 3.0 * 2.0 * math.pi / a
+    mill, right, left = random_orbitals(lat, kmesh, ecut, nb, sigma,
+                                        SEED_BASE + seed_offset, left_mix)
+    A = rpa_A(omega, nelec)
+    kc = math.sqrt(2.0 * ecut)
+    nk = int(np.prod(kmesh))
+    occs = [np.ones(nb) if occ is None else np.asarray(occ, dtype=np.float64) for _ in range(nk)]
+    return Workload(f"fcc_si_x{supercell}_k{'x'.join(map(str, kmesh))}_g{grid}",
+                    lat, tuple(kmesh), (grid,) * 3 if np.isscalar(grid) else tuple(grid),
+                    mill, right, left, occs, (A, A), cusp_C(A), 10.0 / kc ** 2, nelec)
+
+
+def config(i: int) -> Workload:
+    """The five named workloads (1-based), at full size."""
+    if i == 1:
+        return heg_gamma()
+    if i == 2 or i == 5:
+        return fcc_si()
+    if i == 3:
+        return heg_twist()
+    if i == 4:
+        return fcc_si(kmesh=(2, 2, 2), grid=48, nb=32, supercell=2, seed_offset=4)
+    raise ValueError(i)
+
+
+def tiny_fcc(kmesh=(2, 1, 1), grid=8, ecut=1.2, nb=2, a=6.0, seed_offset=100,
+             left_mix=None, occ=None, A=None, C=None, alpha=None) -> Workload:
+    """A small random problem the oracle finishes in well under a second."""
+    w = fcc_si(kmesh=kmesh, grid=grid, ecut=ecut, nb=nb, a=a, seed_offset=seed_offset,
+               left_mix=left_mix, occ=occ)
+    repl = {"name": f"tiny_fcc_k{'x'.join(map(str, kmesh))}_g{grid}"}
+    if A is not None:
+        repl["A"] = tuple(A)
+    if C is not None:
+        repl["C"] = tuple(C)
+    if alpha is not None:
+        repl["alpha"] = alpha
+    return w.replace(**repl)

@@ -1,0 +1,46 @@
+"""The oracle gradient (autograd of the discrete energy) against central finite differences, h = 1e-5."""
+import numpy as np
+import pytest
+
+import tcinputs as T
+from oracle import grad as OG
+
+
+@pytest.fixture(scope="module")
+def case():
+    w = T.tiny_fcc(kmesh=(2, 1, 1), grid=8, ecut=2.0, nb=2, a=6.0, occ=[1.0, 0.6])
+    return w, OG.energy_and_grad(w)
+
+
+def test_orbital_gradient_matches_central_differences(case):
+    w, (E, gc, gA, gC) = case
+    rng = np.random.default_rng(1)
+    h = 1e-5
+    for trial in range(3):
+        d = [rng.standard_normal(c.shape) + 1j * rng.standard_normal(c.shape) for c in w.right]
+        ep = OG.energy(w, coeff=[c + h * x for c, x in zip(w.right, d)])
+        em = OG.energy(w, coeff=[c - h * x for c, x in zip(w.right, d)])
+        fd = (ep - em) / (2 * h)
+        an = sum(np.sum((np.conj(g) * x).real) for g, x in zip(gc, d))
+        assert an == pytest.approx(fd, rel=1e-6, abs=1e-9)
+
+
+@pytest.mark.parametrize("which", ["A0", "A1", "C0", "C1"])
+def test_jastrow_parameter_gradient(case, which):
+    w, (E, gc, gA, gC) = case
+    h = 1e-5
+    A = np.array(w.A, dtype=float)
+    C = np.array(w.C, dtype=float)
+    i = int(which[1])
+    if which[0] == "A":
+        Ap, Am = A.copy(), A.copy()
+        Ap[i] += h
+        Am[i] -= h
+        fd = (OG.energy(w, A=Ap, C=C) - OG.energy(w, A=Am, C=C)) / (2 * h)
+        assert gA[i] == pytest.approx(fd, rel=1e-6, abs=1e-9)
+    else:
+        Cp, Cm = C.copy(), C.copy()
+        Cp[i] += h
+        Cm[i] -= h
+        fd = (OG.energy(w, A=A, C=Cp) - OG.energy(w, A=A, C=Cm)) / (2 * h)
+        assert gC[i] == pytest.approx(fd, rel=1e-6, abs=1e-9)
