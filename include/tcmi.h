@@ -1,0 +1,164 @@
+/* tcmi.h - C ABI of the MI355X transcorrelated-operator library.
+ *
+ * The library applies the two- and three-body terms of the transcorrelated
+ * (TC) effective one-body operator h of arXiv:2302.07420 (Sec. 2.1, Eq. SCF;
+ * terms of Sec. 2.6.2-2.6.4) to every occupied orbital of a spin-unpolarized
+ * plane-wave problem on a uniform Gamma-centred k-mesh, by the FFT pair-density
+ * route of the paper's algorithms (Algs. 2ah, 2ax, 3a1-3a4, 3b1-3b6) with the
+ * Gygi-Baldereschi divergence corrections for k-points on the SCF mesh
+ * (Sec. 2.5; Eqs. divcorr_2ax_scf, divcor_3a2_first/second in their
+ * general-overlap form, 3b6_div_scf1-3).  It also returns the TC pseudo-energy
+ * (Eq. EtotTC) and its gradient with respect to the orbital coefficients and
+ * the Jastrow parameters A and C of Eq. Jastrow.
+ *
+ * Conventions shared by every call
+ *  - All calls return an int status: TC_OK (0) or a negative TC_ERR_* code;
+ *    tc_last_error() then describes the failure.  No exception crosses the ABI.
+ *  - A context is not internally synchronised: use one context per thread.
+ *  - Lattice rows a1, a2, a3 are in bohr; reciprocal rows b_j satisfy
+ *    a_i . b_j = 2 pi delta_ij.  k-point ik = (i1*n2 + i2)*n3 + i3 sits at
+ *    k = (i1/n1, i2/n2, i3/n3) in units of b (Gamma-centred mesh).
+ *  - Orbital coefficients c(G) are complex128, interleaved (re, im), band-major:
+ *    [band][npw(ik)], for the cell-periodic part phi(r) = Omega^{-1/2}
+ *    sum_G c(G) e^{iG.r} (Sec. 2.3 with sum |c|^2 = 1).  G = m1 b1 + m2 b2 + m3 b3
+ *    with the Miller indices given to tc_set_basis.
+ *  - Host buffers passed in are only read during the call (borrowed); host
+ *    output buffers are written before the call returns.  Device pointers
+ *    (the *_dev calls) belong to the caller, are read/written in stream order on
+ *    the context's stream and must stay alive until that stream reaches the
+ *    work; call tc_sync() to wait.
+ *  - Energies are in hartree per cell, summed over both spin channels.
+ */
+#ifndef TCMI_H
+#define TCMI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct tc_ctx tc_ctx;
+
+enum {
+  TC_OK = 0,
+  TC_ERR_ARG = -1,          /* invalid argument (null pointer, out-of-range value)  */
+  TC_ERR_STATE = -2,        /* call made before a required setter                    */
+  TC_ERR_GRID = -3,         /* a plane wave does not fit the FFT grid                */
+  TC_ERR_KMESH = -4,        /* k-mesh / basis inconsistent                           */
+  TC_ERR_UNSUPPORTED = -5,  /* grid size, mode or option not implemented             */
+  TC_ERR_DEVICE = -6,       /* HIP runtime error                                      */
+  TC_ERR_OOM = -7           /* device allocation failed                              */
+};
+
+enum { TC_PREC_FP64 = 0, TC_PREC_FP32 = 1 };
+
+/* Term selection bits for tc_set_options (names follow Sec. 2.6 of the paper).
+ * Three-body terms enter the operator with multiplicity 2 for 3a3, 3a4 and all
+ * 3b terms (3a6 = 3a3, 3a5 = 3a4, 3c* = 3b*).  TC_T_CORR enables the SCF-mesh
+ * divergence corrections of the selected terms (2ax, 3a2, 3b6). */
+enum {
+  TC_T_2AH = 1 << 0, TC_T_2BH1 = 1 << 1, TC_T_2BH2 = 1 << 2,
+  TC_T_2AX = 1 << 3, TC_T_2BX1 = 1 << 4, TC_T_2BX2 = 1 << 5,
+  TC_T_3A1 = 1 << 6, TC_T_3A2 = 1 << 7, TC_T_3A3 = 1 << 8, TC_T_3A4 = 1 << 9,
+  TC_T_3B1 = 1 << 10, TC_T_3B2 = 1 << 11, TC_T_3B3 = 1 << 12, TC_T_3B4 = 1 << 13,
+  TC_T_3B5 = 1 << 14, TC_T_3B6 = 1 << 15,
+  TC_T_CORR = 1 << 16,
+  TC_T_ALL = (1 << 17) - 1
+};
+
+/* Energy breakdown written by tc_energy (hartree per cell, both spins). */
+enum {
+  TC_E_KINETIC = 0,   /* sum f <phi|-lap/2|phi> / N_k                                    */
+  TC_E_TWO_BODY = 1,  /* (1/2) <h2>, h2 = 2ah+2bh1+2bh2+2ax+2bx1+2bx2 (+2ax correction)   */
+  TC_E_THREE_BODY = 2,/* (1/3) <h3>, three-body terms with multiplicities (+ corrections)  */
+  TC_E_CORR = 3,      /* part of the two entries above that comes from the corrections    */
+  TC_E_NPARTS = 4
+};
+
+/* Create a context on HIP device `device`.  `stream` is a hipStream_t owned by
+ * the caller (NULL: the library creates and owns one).  Allocates nothing large
+ * until orbitals are loaded.  TC_ERR_DEVICE if the device is unusable. */
+int tc_create(int device, void* stream, tc_ctx** out);
+
+/* Release every device buffer and the owned stream.  NULL is ignored. */
+void tc_destroy(tc_ctx* ctx);
+
+/* Text of the last error on this context (owned by ctx, valid until the next call). */
+const char* tc_last_error(const tc_ctx* ctx);
+
+/* Lattice rows a1, a2, a3 (bohr); Omega = |det| must be > 0 (TC_ERR_ARG). */
+int tc_set_cell(tc_ctx* ctx, const double lattice[9]);
+
+/* Uniform Gamma-centred Monkhorst-Pack mesh n1 x n2 x n3 (Sec. 2.5 assumes a
+ * uniform SCF mesh).  Each n_i in [1, 16]. */
+int tc_set_kmesh(tc_ctx* ctx, int n1, int n2, int n3);
+
+/* FFT grid.  This build supports cubic grids N1 = N2 = N3 = N with
+ * N in {8, 12, 16, 24, 32, 48}; anything else is TC_ERR_UNSUPPORTED. */
+int tc_set_grid(tc_ctx* ctx, int N1, int N2, int N3);
+
+/* Plane-wave set of k-point ik: npw Miller triples (m1,m2,m3) (int32, [npw][3]).
+ * TC_ERR_GRID if a triple does not fit the grid (|m_i| >= N/2); the grid should
+ * also satisfy N/2 >= 2 max|m_i| + 1 for alias-free pair densities (not checked). */
+int tc_set_basis(tc_ctx* ctx, int ik, int npw, const int32_t* miller);
+
+/* Jastrow parameters of Eq. Jastrow: index 0 = parallel spins, 1 = antiparallel.
+ * A >= 0 (A = 0 gives Hartree-Fock), C > 0.  The cusp relation of Eq. cusp is
+ * the caller's choice (A and C are independent here). */
+int tc_set_jastrow(tc_ctx* ctx, const double A[2], const double C[2]);
+
+/* precision: TC_PREC_FP64 or TC_PREC_FP32 (FFT butterflies, pair products and
+ * kernel multiplies in that precision; corrections, overlaps, partner sums and
+ * energy reductions always FP64).  alpha: exponent of the auxiliary function
+ * exp(-alpha q^2)/q^2 of Eq. aux (bohr^2, > 0).  div_correction: 0/1.
+ * term_mask: OR of TC_T_* bits. */
+int tc_set_options(tc_ctx* ctx, int precision, double alpha, int div_correction, uint64_t term_mask);
+
+/* Copy the occupied orbitals of k-point ik to the device: `right` holds nband x
+ * npw(ik) complex128 coefficients, `left` must be NULL (TC mode, chi = phi; the
+ * biorthogonal mode is not built in this version: TC_ERR_UNSUPPORTED), `occ`
+ * holds nband fillings per spin-orbital in [0, 1].  nband must be the same for
+ * every k-point.  The coefficients are used as given (no re-orthonormalisation). */
+int tc_load_orbitals(tc_ctx* ctx, int ik, int nband, const double* right, const double* left,
+                     const double* occ);
+
+/* Same, from a device buffer (complex128, [nband][npw(ik)]); occ stays on the host. */
+int tc_load_orbitals_dev(tc_ctx* ctx, int ik, int nband, const void* right_dev, const double* occ);
+
+/* Apply the selected two- and three-body terms (with corrections) to every
+ * loaded orbital.  `out` (host) receives [nk][nband][npw_max] complex128
+ * coefficients (H c)(G) = sqrt(Omega) FT[g](G) on each k-point's plane-wave set,
+ * zero-padded to npw_max = max npw.  The energies of this application are kept
+ * for tc_energy. */
+int tc_apply_all(tc_ctx* ctx, double* out);
+
+/* Same, writing to a caller-owned device buffer of the same layout (may be NULL:
+ * the result then stays inside the context).  Asynchronous on the stream. */
+int tc_apply_all_dev(tc_ctx* ctx, void* out_dev);
+
+/* Pseudo-energy per cell (reading of Eq. EtotTC: (1/N_k) Re sum_{sigma,k,mu} f
+ * <phi| T + h2/2 + h3/3 |phi>) of the last application (runs one if needed).
+ * e_parts: NULL or TC_E_NPARTS doubles. */
+int tc_energy(tc_ctx* ctx, double* e_total, double* e_parts);
+
+/* Gradient of the pseudo-energy: grad (host, [nk][nband][npw_max] complex128)
+ * receives dE/dRe c + i dE/dIm c = 2 dE/dc* for the coefficients shared by both
+ * spin channels; dA / dC (may be NULL) receive dE/dA_s and dE/dC_s with the four
+ * parameters independent.  Pair densities are recomputed, not stored. */
+int tc_energy_backward(tc_ctx* ctx, double* grad, double dA[2], double dC[2]);
+
+/* Wait for all work queued by this context. */
+int tc_sync(tc_ctx* ctx);
+
+/* Milliseconds of device time of the last tc_apply_all*, measured with events on
+ * the context's stream; kernel_ms[0..n) receives the per-stage breakdown
+ * (stages: 0 G->r, 1 densities and Hartree fields, 2 occupied-occupied pass,
+ * 3 pass A, 4 pass B, 5 r->G and FP64 corrections). */
+int tc_last_timing(tc_ctx* ctx, double* total_ms, double* stage_ms, int n);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TCMI_H */

@@ -1,0 +1,200 @@
+"""MI355X transcorrelated-operator library: thin Python binding of libtcmi.so.
+
+Argument marshalling only: every step of the operator runs in the HIP library
+(include/tcmi.h).  The library must have been built (``build.py``); importing
+this package without it raises, there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIBPATH = os.path.join(HERE, "libtcmi.so")
+
+TC_PREC_FP64 = 0
+TC_PREC_FP32 = 1
+
+TERM_BITS = {
+    "2ah": 1 << 0, "2bh1": 1 << 1, "2bh2": 1 << 2, "2ax": 1 << 3, "2bx1": 1 << 4, "2bx2": 1 << 5,
+    "3a1": 1 << 6, "3a2": 1 << 7, "3a3": 1 << 8, "3a4": 1 << 9, "3b1": 1 << 10, "3b2": 1 << 11,
+    "3b3": 1 << 12, "3b4": 1 << 13, "3b5": 1 << 14, "3b6": 1 << 15, "corr": 1 << 16,
+}
+TERM_ALL = (1 << 17) - 1
+E_PARTS = ("kinetic", "two_body", "three_body", "corrections")
+
+_lib = None
+
+
+class TCError(RuntimeError):
+    pass
+
+
+def lib():
+    """Load libtcmi.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIBPATH):
+        raise TCError(f"{LIBPATH} not found: build it with paper_2302_07420_amd/build.py")
+    L = ctypes.CDLL(LIBPATH)
+    P, I, D = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
+    dp = ctypes.POINTER(ctypes.c_double)
+    sig = {
+        "tc_create": (I, [I, P, ctypes.POINTER(P)]),
+        "tc_destroy": (None, [P]),
+        "tc_last_error": (ctypes.c_char_p, [P]),
+        "tc_set_cell": (I, [P, dp]),
+        "tc_set_kmesh": (I, [P, I, I, I]),
+        "tc_set_grid": (I, [P, I, I, I]),
+        "tc_set_basis": (I, [P, I, I, ctypes.POINTER(ctypes.c_int32)]),
+        "tc_set_jastrow": (I, [P, dp, dp]),
+        "tc_set_options": (I, [P, I, D, I, ctypes.c_uint64]),
+        "tc_load_orbitals": (I, [P, I, I, dp, dp, dp]),
+        "tc_load_orbitals_dev": (I, [P, I, I, P, dp]),
+        "tc_apply_all": (I, [P, dp]),
+        "tc_apply_all_dev": (I, [P, P]),
+        "tc_energy": (I, [P, dp, dp]),
+        "tc_energy_backward": (I, [P, dp, dp, dp]),
+        "tc_sync": (I, [P]),
+        "tc_last_timing": (I, [P, dp, dp, I]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+def _dp(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+class TCOperator:
+    """One problem on one device.  Mirrors the C ABI call for call."""
+
+    def __init__(self, device: int = 0, stream: Optional[int] = None):
+        self._L = lib()
+        h = ctypes.c_void_p()
+        st = self._L.tc_create(device, ctypes.c_void_p(stream) if stream else None, ctypes.byref(h))
+        if st != 0:
+            raise TCError(f"tc_create failed with status {st}")
+        self._h = h
+        self.npw: List[int] = []
+        self.nband = 0
+
+    def _check(self, st: int, what: str):
+        if st != 0:
+            msg = self._L.tc_last_error(self._h).decode()
+            raise TCError(f"{what}: status {st}: {msg}")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._L.tc_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---------------------------------------------------------------- setters
+    def set_cell(self, lattice):
+        a = np.ascontiguousarray(np.asarray(lattice, dtype=np.float64).reshape(9))
+        self._check(self._L.tc_set_cell(self._h, _dp(a)), "tc_set_cell")
+
+    def set_kmesh(self, n1, n2, n3):
+        self._check(self._L.tc_set_kmesh(self._h, n1, n2, n3), "tc_set_kmesh")
+        self.npw = [0] * (n1 * n2 * n3)
+
+    def set_grid(self, N1, N2, N3):
+        self._check(self._L.tc_set_grid(self._h, N1, N2, N3), "tc_set_grid")
+
+    def set_basis(self, ik, miller):
+        m = np.ascontiguousarray(np.asarray(miller, dtype=np.int32).reshape(-1, 3))
+        self._check(self._L.tc_set_basis(self._h, ik, m.shape[0], m.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))),
+                    "tc_set_basis")
+        self.npw[ik] = m.shape[0]
+
+    def set_jastrow(self, A, C):
+        a = np.ascontiguousarray(np.asarray(A, dtype=np.float64))
+        c = np.ascontiguousarray(np.asarray(C, dtype=np.float64))
+        self._check(self._L.tc_set_jastrow(self._h, _dp(a), _dp(c)), "tc_set_jastrow")
+
+    def set_options(self, precision=TC_PREC_FP64, alpha=1.0, div_correction=True, terms=TERM_ALL):
+        self._check(self._L.tc_set_options(self._h, int(precision), float(alpha), int(bool(div_correction)),
+                                           int(terms)), "tc_set_options")
+
+    def load_orbitals(self, ik, coeff, occ):
+        c = np.ascontiguousarray(np.asarray(coeff, dtype=np.complex128))
+        o = np.ascontiguousarray(np.asarray(occ, dtype=np.float64))
+        self.nband = c.shape[0]
+        self._check(self._L.tc_load_orbitals(self._h, ik, c.shape[0], _dp(c.view(np.float64)), None, _dp(o)),
+                    "tc_load_orbitals")
+
+    def load_orbitals_dev(self, ik, ptr: int, nband: int, occ):
+        o = np.ascontiguousarray(np.asarray(occ, dtype=np.float64))
+        self.nband = nband
+        self._check(self._L.tc_load_orbitals_dev(self._h, ik, nband, ctypes.c_void_p(ptr), _dp(o)),
+                    "tc_load_orbitals_dev")
+
+    # ---------------------------------------------------------------- work
+    @property
+    def npw_max(self):
+        return max(self.npw)
+
+    def apply(self) -> List[np.ndarray]:
+        nk = len(self.npw)
+        out = np.zeros((nk, self.nband, self.npw_max), dtype=np.complex128)
+        self._check(self._L.tc_apply_all(self._h, _dp(out.view(np.float64))), "tc_apply_all")
+        return [out[k, :, : self.npw[k]] for k in range(nk)]
+
+    def apply_dev(self, out_ptr: Optional[int] = None):
+        self._check(self._L.tc_apply_all_dev(self._h, ctypes.c_void_p(out_ptr) if out_ptr else None),
+                    "tc_apply_all_dev")
+
+    def energy(self):
+        e = np.zeros(1)
+        parts = np.zeros(len(E_PARTS))
+        self._check(self._L.tc_energy(self._h, _dp(e), _dp(parts)), "tc_energy")
+        return float(e[0]), dict(zip(E_PARTS, parts.tolist()))
+
+    def backward(self):
+        nk = len(self.npw)
+        g = np.zeros((nk, self.nband, self.npw_max), dtype=np.complex128)
+        dA = np.zeros(2)
+        dC = np.zeros(2)
+        self._check(self._L.tc_energy_backward(self._h, _dp(g.view(np.float64)), _dp(dA), _dp(dC)),
+                    "tc_energy_backward")
+        return [g[k, :, : self.npw[k]] for k in range(nk)], dA, dC
+
+    def sync(self):
+        self._check(self._L.tc_sync(self._h), "tc_sync")
+
+    def timing(self):
+        tot = np.zeros(1)
+        st = np.zeros(6)
+        self._check(self._L.tc_last_timing(self._h, _dp(tot), _dp(st), 6), "tc_last_timing")
+        return float(tot[0]), st.tolist()
+
+
+def from_workload(w, precision=TC_PREC_FP64, terms=TERM_ALL, div_correction=True, device=0, A=None, C=None,
+                  coeff=None) -> TCOperator:
+    """Build an operator from a ``tcinputs.Workload`` (TC mode)."""
+    op = TCOperator(device)
+    op.set_cell(w.lattice)
+    op.set_kmesh(*w.kmesh)
+    op.set_grid(*w.grid)
+    for ik, m in enumerate(w.miller):
+        op.set_basis(ik, m)
+    op.set_jastrow(w.A if A is None else A, w.C if C is None else C)
+    op.set_options(precision, w.alpha, div_correction, terms)
+    cs = w.right if coeff is None else coeff
+    for ik in range(len(w.miller)):
+        op.load_orbitals(ik, cs[ik], w.occ[ik])
+    return op

@@ -1,0 +1,1183 @@
+// Host orchestration, FP64 set-up and corrections, and the C ABI (include/tcmi.h).
+//
+// One context owns one problem (cell, k-mesh, grid, basis, Jastrow parameters,
+// options, orbitals) and an engine specialised on the working precision R and the
+// grid length N.  An application runs, on the context's stream:
+//   0  G -> r of psi = sqrt(Omega) phi and D = sqrt(Omega) (nabla + ik) phi;
+//   1  densities n, J and the Hartree-type fields (Algs. 2ah, 3a1, 3b1; 2bh1/2bh2);
+//   2  occupied-occupied pair pass (Algs. 3a2, 3a4 first loop, 3b2/3b5 first loop);
+//   3  pass A per (target j, partner q): 2ax, 2bx1, 3a4, h4_j (Algs. 2ax, 3a3), 3b6 chain;
+//   4  pass B per pair: 2bx2 + 2*(3b3 + 3b4 + 3b5) through one shared kernel -iQu;
+//   5  local terms, r -> G, then the SCF-mesh divergence corrections in FP64.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/tcmi.h"
+#include "kernels.hpp"
+
+using namespace tcmi;
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+constexpr double kFourPi = 4.0 * kPi;
+
+#define TC_HIP(call)                                                                     \
+  do {                                                                                   \
+    hipError_t e_ = (call);                                                              \
+    if (e_ != hipSuccess) {                                                              \
+      throw TcError(TC_ERR_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_));   \
+    }                                                                                    \
+  } while (0)
+
+struct TcError {
+  int code;
+  std::string msg;
+  TcError(int c, std::string m) : code(c), msg(std::move(m)) {}
+};
+
+// ------------------------------------------------------------------ kernels of u = A/r (1 - e^{-r/C})
+// Fourier transforms of Sec. 2.6.2 and Appendix B (non-periodic convention).
+struct Jk {
+  double u, lap, w;
+};
+
+inline Jk jastrow_ft(double Q2, double A, double C) {
+  const double ic2 = 1.0 / (C * C);
+  Jk k;
+  k.u = kFourPi * A * (1.0 / Q2 - 1.0 / (Q2 + ic2));
+  k.lap = -kFourPi * A * ic2 / (Q2 + ic2);
+  const double g = C * std::sqrt(Q2);
+  double br;
+  if (g < 1e-3) {
+    const double g2 = g * g;   // Taylor series of the bracket / g
+    br = 0.5 - kPi * g / 4.0 + 11.0 * g2 / 24.0 - 57.0 * g2 * g2 / 480.0;
+  } else {
+    br = (-kPi * g * g / 4.0 - (1.0 + 0.5 * g * g) * std::atan(0.5 * g) + (1.0 + g * g) * std::atan(g)) / g;
+  }
+  k.w = kFourPi * A * A / C * br;
+  return k;
+}
+
+// ------------------------------------------------------------------ problem description (host, FP64)
+struct Problem {
+  double lat[9] = {0};
+  double B[9] = {0};
+  double omega = 0;
+  bool cell = false;
+  int n1 = 0, n2 = 0, n3 = 0, nk = 0;
+  int N = 0;
+  std::vector<std::vector<int>> miller;   // per k, 3*npw
+  std::vector<int> npw;
+  int npw_max = 0;
+  double A[2] = {0, 0}, C[2] = {1, 1};
+  bool jastrow = false;
+  int prec = TC_PREC_FP64;
+  double alpha = 1.0;
+  int div = 1;
+  uint64_t mask = TC_T_ALL;
+  bool options = false;
+  int nb = 0;
+  std::vector<double> occ;                // [nk][nb]
+  std::vector<char> loaded;               // per k
+  double delta_gb = 0, sigma_aux = 0;
+
+  int P() const { return nk * nb; }
+  long NR() const { return long(N) * N * N; }
+  void kfrac(int ik, double* f) const {
+    const int i3 = ik % n3, i2 = (ik / n3) % n2, i1 = ik / (n3 * n2);
+    f[0] = double(i1) / n1;
+    f[1] = double(i2) / n2;
+    f[2] = double(i3) / n3;
+  }
+};
+
+inline int mfreq_h(int i, int N) { return i < N / 2 ? i : i - N; }
+
+// Gygi-Baldereschi bracket of Eq. correction2 with A_aux = e^{-alpha q^2}/q^2 (Eq. aux),
+// summed over the mesh and the ball exp(-alpha |k-q+G|^2) > 1e-18 (uniform mesh: k = 0).
+void gb_constant(Problem& pb) {
+  const double a = pb.alpha;
+  const double qmax = std::sqrt(41.45 / a);
+  int mm[3];
+  for (int i = 0; i < 3; ++i) {
+    const double L = std::sqrt(pb.lat[3 * i] * pb.lat[3 * i] + pb.lat[3 * i + 1] * pb.lat[3 * i + 1] +
+                               pb.lat[3 * i + 2] * pb.lat[3 * i + 2]);
+    mm[i] = int(std::ceil(qmax * L / (2 * kPi))) + 2;
+  }
+  double sum = 0, comp = 0;   // Neumaier summation
+  for (int ik = 0; ik < pb.nk; ++ik) {
+    double f[3];
+    pb.kfrac(ik, f);
+    for (int m1 = -mm[0]; m1 <= mm[0]; ++m1)
+      for (int m2 = -mm[1]; m2 <= mm[1]; ++m2)
+        for (int m3 = -mm[2]; m3 <= mm[2]; ++m3) {
+          const double c1 = m1 - f[0], c2 = m2 - f[1], c3 = m3 - f[2];
+          double Q[3];
+          for (int c = 0; c < 3; ++c) Q[c] = c1 * pb.B[c] + c2 * pb.B[3 + c] + c3 * pb.B[6 + c];
+          const double q2 = Q[0] * Q[0] + Q[1] * Q[1] + Q[2] * Q[2];
+          if (q2 <= 1e-20 || a * q2 >= 41.45) continue;
+          const double t = std::exp(-a * q2) / q2;
+          const double s = sum + t;
+          comp += std::fabs(sum) >= std::fabs(t) ? (sum - s) + t : (t - s) + sum;
+          sum = s;
+        }
+  }
+  pb.sigma_aux = sum + comp;
+  pb.delta_gb = pb.omega / (4.0 * std::sqrt(kPi * kPi * kPi * a)) - (-a + pb.sigma_aux) / pb.nk;
+}
+
+// ------------------------------------------------------------------ device buffers
+template <typename T>
+struct DBuf {
+  T* p = nullptr;
+  size_t n = 0;
+  void alloc(size_t count) {
+    if (count <= n && p) return;
+    release();
+    if (count == 0) return;
+    hipError_t e = hipMalloc(&p, count * sizeof(T));
+    if (e != hipSuccess) {
+      p = nullptr;
+      throw TcError(TC_ERR_OOM, "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed");
+    }
+    n = count;
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    n = 0;
+  }
+  ~DBuf() { release(); }
+};
+
+struct Shared {                       // precision-independent device data
+  DBuf<double> coef;                  // [P][npw_max] complex128
+  DBuf<int> boxidx;                   // [nk][npw_max]
+  DBuf<int> npw;                      // [nk]
+  DBuf<double> kg;                    // [nk][npw_max][3]
+  DBuf<double> w;                     // [P]  f / N_k
+  DBuf<double> dfr;                   // [nDelta][3]
+  DBuf<double> out;                   // [P][npw_max] complex128 (H c)
+  DBuf<double> dhc2, dhc3;            // FP64 corrections
+  DBuf<double> epart;                 // [P][4]
+  DBuf<double> tkin;                  // [P]
+  DBuf<double> S;                     // [nk][nb][nb] complex overlaps
+  DBuf<double> O;                     // [nk][nb][nb] complex <c_mu | Z_j>
+  DBuf<double> Zg, Wg;                // [P][npw_max] complex
+  DBuf<double> ecorr;                 // [P][2]
+};
+
+// ------------------------------------------------------------------ FP64 helper kernels
+__global__ void k_overlap(const double* a, const double* b, const int* npw, int nb, int npw_max, int nk, double* S) {
+  // S[k][m][n] = sum_g conj(a_km[g]) b_kn[g]
+  const int id = blockIdx.x;
+  const int k = id / (nb * nb), m = (id / nb) % nb, n = id % nb;
+  const double* x = a + 2 * (long(k * nb + m) * npw_max);
+  const double* y = b + 2 * (long(k * nb + n) * npw_max);
+  double sr = 0, si = 0;
+  for (int g = threadIdx.x; g < npw[k]; g += blockDim.x) {
+    sr += x[2 * g] * y[2 * g] + x[2 * g + 1] * y[2 * g + 1];
+    si += x[2 * g] * y[2 * g + 1] - x[2 * g + 1] * y[2 * g];
+  }
+  __shared__ double rr[256], ri[256];
+  rr[threadIdx.x] = sr;
+  ri[threadIdx.x] = si;
+  __syncthreads();
+  for (int h = blockDim.x / 2; h > 0; h >>= 1) {
+    if (int(threadIdx.x) < h) {
+      rr[threadIdx.x] += rr[threadIdx.x + h];
+      ri[threadIdx.x] += ri[threadIdx.x + h];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    S[2 * id] = rr[0];
+    S[2 * id + 1] = ri[0];
+  }
+}
+
+__global__ void k_kinetic(const double* c, const double* kg, const int* npw, int nb, int npw_max, double* t) {
+  const int p = blockIdx.x, k = p / nb;
+  double s = 0;
+  for (int g = threadIdx.x; g < npw[k]; g += blockDim.x) {
+    const double* q = kg + (long(k) * npw_max + g) * 3;
+    const double e = 0.5 * (q[0] * q[0] + q[1] * q[1] + q[2] * q[2]);
+    const double* x = c + 2 * (long(p) * npw_max + g);
+    s += e * (x[0] * x[0] + x[1] * x[1]);
+  }
+  __shared__ double red[256];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int h = blockDim.x / 2; h > 0; h >>= 1) {
+    if (int(threadIdx.x) < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) t[p] = red[0];
+}
+
+// Source of the G != 0 correction of 3a2 (Eq. divcor_3a2_second, general-overlap form):
+// Y = 2 sum_k sum_{m1,m2} (f_m1 f_m2 / N_k) (S(m1,m2)/Omega) conj(psi_m2) psi_m1   (TC mode)
+template <int N>
+__global__ void k_corr_Ysrc(const cx<double>* psi, const double* S, const double* f, int nk, int nb, double inv_nk_omega,
+                            cx<double>* Y) {
+  constexpr long NR = long(N) * N * N;
+  const long r = long(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (r >= NR) return;
+  double yr = 0, yi = 0;
+  for (int k = 0; k < nk; ++k)
+    for (int m1 = 0; m1 < nb; ++m1)
+      for (int m2 = 0; m2 < nb; ++m2) {
+        const int i1 = k * nb + m1, i2 = k * nb + m2;
+        const double sr = S[2 * ((k * nb + m1) * nb + m2)], si = S[2 * ((k * nb + m1) * nb + m2) + 1];
+        const cx<double> v = cmulc(psi[i2 * NR + r], psi[i1 * NR + r]);
+        const double c = 2.0 * f[i1] * f[i2] * inv_nk_omega;
+        yr += c * (sr * v.x - si * v.y);
+        yi += c * (sr * v.y + si * v.x);
+      }
+  Y[r] = {yr, yi};
+}
+
+// G-space fields of the corrections: F3b6~ = sum_s (2 pi A_s / N_k) u_s n~, F2~ = sum_s (4 pi A_s / N_k) u_s Y~
+template <int N>
+__global__ void k_corr_gfields(const double* u0, const double* u1, double c0, double c1, const cx<double>* in,
+                               cx<double>* out) {
+  constexpr long NR = long(N) * N * N;
+  const long r = long(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (r >= NR) return;
+  out[r] = (c0 * u0[r] + c1 * u1[r]) * in[r];
+}
+
+// per-orbital products F * psi_p for two fields (batched output [2][P][NR])
+template <int N>
+__global__ void k_corr_products(const cx<double>* F, const cx<double>* psi, int P, cx<double>* out) {
+  constexpr long NR = long(N) * N * N;
+  const long id = long(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (id >= 2L * P * NR) return;
+  const long fi = id / (long(P) * NR);
+  const long rem = id - fi * long(P) * NR;
+  const long p = rem / NR, r = rem - p * NR;
+  out[id] = F[fi * NR + r] * psi[p * NR + r];
+}
+
+// corrections in coefficient space (FP64):
+//  dhc2_j = -4 pi dGB sum_mu f_mu (S(mu,j)/Omega) c_mu                        (Eq. divcorr_2ax_scf)
+//  dhc3_j = 1/2 const1 c_j + 1/2 W_j                                          (3a2, Eqs. divcor_3a2_*)
+//         + 2 sum_mu f_mu { [c1s n0 S(mu,j)/Omega + O(mu,j)/Omega] c_mu + (S(mu,j)/Omega) Z_mu }  (3b6 x 2)
+__global__ void k_corr_apply(const double* c, const double* S, const double* O, const double* Z, const double* W,
+                             const double* f, const int* npw, int nb, int npw_max, int P, double omega, double m2ax,
+                             double dgb, double m3a2, double const1, double m3b6, double c1s_n0, double* dhc2,
+                             double* dhc3) {
+  const long id = long(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (id >= long(P) * npw_max) return;
+  const int j = int(id / npw_max), g = int(id - long(j) * npw_max);
+  const int k = j / nb, jb = j % nb;
+  double a2r = 0, a2i = 0, a3r = 0, a3i = 0;
+  if (g < npw[k]) {
+    const double* cj = c + 2 * (long(j) * npw_max + g);
+    for (int mu = 0; mu < nb; ++mu) {
+      const int q = k * nb + mu;
+      const double* cq = c + 2 * (long(q) * npw_max + g);
+      const double* zq = Z + 2 * (long(q) * npw_max + g);
+      const long si = 2 * ((long(k) * nb + mu) * nb + jb);
+      const double sr = S[si] / omega, sim = S[si + 1] / omega;
+      const double orr = O[si] / omega, oi = O[si + 1] / omega;
+      // 2ax
+      a2r += -kFourPi * dgb * f[q] * (sr * cq[0] - sim * cq[1]);
+      a2i += -kFourPi * dgb * f[q] * (sr * cq[1] + sim * cq[0]);
+      // 3b6 (x 2)
+      const double br = c1s_n0 * sr + orr, bi = c1s_n0 * sim + oi;
+      a3r += 2.0 * m3b6 * f[q] * (br * cq[0] - bi * cq[1] + sr * zq[0] - sim * zq[1]);
+      a3i += 2.0 * m3b6 * f[q] * (br * cq[1] + bi * cq[0] + sr * zq[1] + sim * zq[0]);
+    }
+    const double* wj = W + 2 * (long(j) * npw_max + g);
+    a3r += m3a2 * 0.5 * (const1 * cj[0] + wj[0]);
+    a3i += m3a2 * 0.5 * (const1 * cj[1] + wj[1]);
+  }
+  dhc2[2 * id] = m2ax * a2r;
+  dhc2[2 * id + 1] = m2ax * a2i;
+  dhc3[2 * id] = a3r;
+  dhc3[2 * id + 1] = a3i;
+}
+
+// out += dhc2 + dhc3;  ecorr[j] = (<c_j|dhc2_j>, <c_j|dhc3_j>) real parts
+__global__ void k_corr_add(const double* c, const double* dhc2, const double* dhc3, const int* npw, int nb,
+                           int npw_max, double* out, double* ecorr) {
+  const int j = blockIdx.x, k = j / nb;
+  double e2 = 0, e3 = 0;
+  for (int g = threadIdx.x; g < npw_max; g += blockDim.x) {
+    const long o = 2 * (long(j) * npw_max + g);
+    if (g < npw[k]) {
+      e2 += c[o] * dhc2[o] + c[o + 1] * dhc2[o + 1];
+      e3 += c[o] * dhc3[o] + c[o + 1] * dhc3[o + 1];
+      out[o] += dhc2[o] + dhc3[o];
+      out[o + 1] += dhc2[o + 1] + dhc3[o + 1];
+    }
+  }
+  __shared__ double r2[256], r3[256];
+  r2[threadIdx.x] = e2;
+  r3[threadIdx.x] = e3;
+  __syncthreads();
+  for (int h = blockDim.x / 2; h > 0; h >>= 1) {
+    if (int(threadIdx.x) < h) {
+      r2[threadIdx.x] += r2[threadIdx.x + h];
+      r3[threadIdx.x] += r3[threadIdx.x + h];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    ecorr[2 * j] = r2[0];
+    ecorr[2 * j + 1] = r3[0];
+  }
+}
+
+
+// density only (FP64 corrections): n = sum_q w_q |psi_q|^2
+template <int N>
+__global__ void k_density64(const cx<double>* psi, const double* w, int P, cx<double>* n) {
+  constexpr long NR = long(N) * N * N;
+  const long r = long(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (r >= NR) return;
+  double s = 0;
+  for (int q = 0; q < P; ++q) {
+    const cx<double> a = psi[q * NR + r];
+    s += w[q] * (a.x * a.x + a.y * a.y);
+  }
+  n[r] = {s, 0.0};
+}
+
+inline unsigned nblk(long n, int b = 256) { return unsigned((n + b - 1) / b); }
+
+// ------------------------------------------------------------------ engine
+struct Engine {
+  virtual ~Engine() = default;
+  virtual void upload_tables(const Problem& pb) = 0;
+  virtual void apply(hipStream_t s, Shared& sh, const Problem& pb, double* stage_ms) = 0;
+};
+
+template <typename R, int N>
+void fft3d_t(cx<R>* d, long nvol, int dir, hipStream_t s) {
+  if (nvol <= 0) return;
+  constexpr int PB = XY<R, N>::PB;
+  const long np = nvol * N;
+  if (dir < 0) {
+    hipLaunchKernelGGL((k_fft_xy<R, N, -1>), dim3(nblk(np, PB)), dim3(PB * N), 0, s, d, np);
+    hipLaunchKernelGGL((k_fft_z<R, N, -1>), dim3(nblk(nvol * N * N)), dim3(256), 0, s, d, nvol);
+  } else {
+    hipLaunchKernelGGL((k_fft_z<R, N, 1>), dim3(nblk(nvol * N * N)), dim3(256), 0, s, d, nvol);
+    hipLaunchKernelGGL((k_fft_xy<R, N, 1>), dim3(nblk(np, PB)), dim3(PB * N), 0, s, d, np);
+  }
+}
+
+Masks make_masks(uint64_t m) {
+  auto b = [&](uint64_t bit) { return (m & bit) ? 1.0 : 0.0; };
+  Masks k;
+  k.m2ah = b(TC_T_2AH); k.m2bh1 = b(TC_T_2BH1); k.m2bh2 = b(TC_T_2BH2);
+  k.m2ax = b(TC_T_2AX); k.m2bx1 = b(TC_T_2BX1); k.m2bx2 = b(TC_T_2BX2);
+  k.m3a1 = b(TC_T_3A1); k.m3a2 = b(TC_T_3A2); k.m3a3 = b(TC_T_3A3); k.m3a4 = b(TC_T_3A4);
+  k.m3b1 = b(TC_T_3B1); k.m3b2 = b(TC_T_3B2); k.m3b3 = b(TC_T_3B3); k.m3b4 = b(TC_T_3B4);
+  k.m3b5 = b(TC_T_3B5); k.m3b6 = b(TC_T_3B6);
+  return k;
+}
+
+struct Events {
+  std::vector<hipEvent_t> e;
+  explicit Events(int n) : e(n, nullptr) {
+    for (auto& x : e) TC_HIP(hipEventCreate(&x));
+  }
+  ~Events() {
+    for (auto& x : e)
+      if (x) (void)hipEventDestroy(x);
+  }
+  float ms(int a, int b) const {
+    float t = 0;
+    TC_HIP(hipEventElapsedTime(&t, e[a], e[b]));
+    return t;
+  }
+};
+
+template <typename R, int N>
+struct EngineT : Engine {
+  static constexpr long NR = long(N) * N * N;
+  static constexpr int PB = XY<R, N>::PB;
+  // working-precision fields
+  DBuf<cx<R>> psi;     // [P][NR]
+  DBuf<cx<R>> D;       // [3][P][NR]
+  DBuf<cx<R>> nJ;      // [4][NR]  n, J_x, J_y, J_z
+  DBuf<cx<R>> loc;     // [8][NR]  VH, h1 x3, P2bh2, F3b1, h6, F3b2
+  DBuf<cx<R>> wk;      // [9][NR]  scratch volumes
+  DBuf<cx<R>> H3a4;    // [P][3][NR]
+  DBuf<R> h5;          // [P][NR]
+  DBuf<cx<R>> bufA;    // [T*P][6][NR]
+  DBuf<cx<R>> bufB;    // [T*P][7][NR]
+  DBuf<cx<R>> h4, Z;   // [T][3][NR]
+  DBuf<cx<R>> g;       // [T][NR]
+  DBuf<cx<double>> acc;  // [4][T][NR]
+  // kernel tables (scaled by 1/(Omega N^3))
+  DBuf<R> tV, tU1, tU2, tHV, tHU;
+  DBuf<double> dfr;
+  // FP64 side of the corrections
+  DBuf<cx<double>> psi64, v64, prod64;
+  DBuf<double> tHu0, tHu1, focc;
+  int T = 1;
+  int P_alloc = -1;
+
+  static bool grid_q(const Problem& pb, long r, const double* f, double* Q, double& q2) {
+    const int x = int(r % N), y = int((r / N) % N), z = int(r / (N * N));
+    const int m1 = mfreq_h(x, N), m2 = mfreq_h(y, N), m3 = mfreq_h(z, N);
+    if (m1 == -N / 2 || m2 == -N / 2 || m3 == -N / 2) return false;   // Nyquist planes carry no kernel
+    const double c1 = (f ? f[0] : 0) + m1, c2 = (f ? f[1] : 0) + m2, c3 = (f ? f[2] : 0) + m3;
+    for (int c = 0; c < 3; ++c) Q[c] = c1 * pb.B[c] + c2 * pb.B[3 + c] + c3 * pb.B[6 + c];
+    q2 = Q[0] * Q[0] + Q[1] * Q[1] + Q[2] * Q[2];
+    return true;
+  }
+
+  // Exchange-type tables at Q = Delta + G: V2a parallel (Q = 0: 1/r dropped, L(0) - W(0)), u~ (Q = 0: 0)
+  static void fill_delta(const Problem& pb, const double* f, double scale, R* V, R* U1, R* U2) {
+    for (long r = 0; r < NR; ++r) {
+      double Q[3], q2;
+      if (!grid_q(pb, r, f, Q, q2)) {
+        V[r] = U1[r] = U2[r] = R(0);
+        continue;
+      }
+      if (q2 < 1e-20) {
+        V[r] = R(scale * (-kFourPi * pb.A[0] - 2.0 * kPi * pb.A[0] * pb.A[0] / pb.C[0]));
+        U1[r] = U2[r] = R(0);
+        continue;
+      }
+      const Jk k0 = jastrow_ft(q2, pb.A[0], pb.C[0]);
+      const Jk k1 = jastrow_ft(q2, pb.A[1], pb.C[1]);
+      V[r] = R(scale * (kFourPi / q2 + k0.lap - k0.w));
+      U1[r] = R(scale * k0.u);
+      U2[r] = R(scale * k1.u);
+    }
+  }
+
+  void upload_tables(const Problem& pb) override {
+    const int nD = (2 * pb.n1 - 1) * (2 * pb.n2 - 1) * (2 * pb.n3 - 1);
+    const double scale = 1.0 / (pb.omega * double(NR));
+    std::vector<R> V(size_t(nD) * NR), U1(size_t(nD) * NR), U2(size_t(nD) * NR);
+    std::vector<double> df(size_t(nD) * 3);
+    for (int d1 = -(pb.n1 - 1); d1 <= pb.n1 - 1; ++d1)
+      for (int d2 = -(pb.n2 - 1); d2 <= pb.n2 - 1; ++d2)
+        for (int d3 = -(pb.n3 - 1); d3 <= pb.n3 - 1; ++d3) {
+          const int di = ((d1 + pb.n1 - 1) * (2 * pb.n2 - 1) + (d2 + pb.n2 - 1)) * (2 * pb.n3 - 1) + (d3 + pb.n3 - 1);
+          const double f[3] = {double(d1) / pb.n1, double(d2) / pb.n2, double(d3) / pb.n3};
+          for (int c = 0; c < 3; ++c) df[3 * di + c] = f[c];
+          fill_delta(pb, f, scale, &V[size_t(di) * NR], &U1[size_t(di) * NR], &U2[size_t(di) * NR]);
+        }
+    tV.alloc(V.size());
+    tU1.alloc(U1.size());
+    tU2.alloc(U2.size());
+    dfr.alloc(df.size());
+    TC_HIP(hipMemcpy(tV.p, V.data(), V.size() * sizeof(R), hipMemcpyHostToDevice));
+    TC_HIP(hipMemcpy(tU1.p, U1.data(), U1.size() * sizeof(R), hipMemcpyHostToDevice));
+    TC_HIP(hipMemcpy(tU2.p, U2.data(), U2.size() * sizeof(R), hipMemcpyHostToDevice));
+    TC_HIP(hipMemcpy(dfr.p, df.data(), df.size() * sizeof(double), hipMemcpyHostToDevice));
+    // Hartree tables (Delta = 0, G = 0 dropped); both spin channels summed for the working precision
+    std::vector<R> HV(NR), HU(NR);
+    std::vector<double> hu0(NR), hu1(NR);
+    for (long r = 0; r < NR; ++r) {
+      double Q[3], q2;
+      if (!grid_q(pb, r, nullptr, Q, q2) || q2 < 1e-20) {
+        HV[r] = HU[r] = R(0);
+        hu0[r] = hu1[r] = 0;
+        continue;
+      }
+      const Jk k0 = jastrow_ft(q2, pb.A[0], pb.C[0]);
+      const Jk k1 = jastrow_ft(q2, pb.A[1], pb.C[1]);
+      const double v = kFourPi / q2;
+      HV[r] = R(scale * ((v + k0.lap - k0.w) + (v + k1.lap - k1.w)));
+      HU[r] = R(scale * (k0.u + k1.u));
+      hu0[r] = scale * k0.u;
+      hu1[r] = scale * k1.u;
+    }
+    tHV.alloc(NR);
+    tHU.alloc(NR);
+    tHu0.alloc(NR);
+    tHu1.alloc(NR);
+    TC_HIP(hipMemcpy(tHV.p, HV.data(), NR * sizeof(R), hipMemcpyHostToDevice));
+    TC_HIP(hipMemcpy(tHU.p, HU.data(), NR * sizeof(R), hipMemcpyHostToDevice));
+    TC_HIP(hipMemcpy(tHu0.p, hu0.data(), NR * sizeof(double), hipMemcpyHostToDevice));
+    TC_HIP(hipMemcpy(tHu1.p, hu1.data(), NR * sizeof(double), hipMemcpyHostToDevice));
+  }
+
+  void ensure(const Problem& pb, size_t budget_bytes) {
+    const int P = pb.P();
+    if (P == P_alloc) return;
+    psi.alloc(size_t(P) * NR);
+    D.alloc(size_t(3) * P * NR);
+    nJ.alloc(4 * NR);
+    loc.alloc(8 * NR);
+    wk.alloc(9 * NR);
+    H3a4.alloc(size_t(3) * P * NR);
+    h5.alloc(size_t(P) * NR);
+    const size_t per_t = size_t(P) * 13 * NR * sizeof(cx<R>);
+    T = int(std::max<size_t>(1, std::min<size_t>(size_t(P), budget_bytes / per_t)));
+    bufA.alloc(size_t(T) * P * 6 * NR);
+    bufB.alloc(size_t(T) * P * 7 * NR);
+    h4.alloc(size_t(3) * T * NR);
+    Z.alloc(size_t(3) * T * NR);
+    g.alloc(size_t(T) * NR);
+    acc.alloc(size_t(4) * T * NR);
+    psi64.alloc(size_t(P) * NR);
+    v64.alloc(4 * NR);
+    prod64.alloc(size_t(2) * P * NR);
+    focc.alloc(P);
+    P_alloc = P;
+  }
+
+  void apply(hipStream_t s, Shared& sh, const Problem& pb, double* stage_ms) override {
+    const int P = pb.P();
+    const int nb = pb.nb;
+    const Masks m = make_masks(pb.mask);
+    ensure(pb, size_t(8) << 30);
+    const MeshInfo mi{pb.n1, pb.n2, pb.n3, nb, P};
+    Recip rc;
+    for (int i = 0; i < 9; ++i) rc.b[i] = pb.B[i];
+    const Tables tb{tV.p, tU1.p, tU2.p, dfr.p};
+    Events ev(8);
+    TC_HIP(hipEventRecord(ev.e[0], s));
+
+    // ---- 0: G -> r (psi and the three components of D)
+    TC_HIP(hipMemsetAsync(psi.p, 0, size_t(P) * NR * sizeof(cx<R>), s));
+    TC_HIP(hipMemsetAsync(D.p, 0, size_t(3) * P * NR * sizeof(cx<R>), s));
+    const unsigned gsc = nblk(long(P) * pb.npw_max);
+    hipLaunchKernelGGL((k_scatter<R>), dim3(gsc), dim3(256), 0, s, sh.coef.p, sh.boxidx.p, sh.npw.p, sh.kg.p, nb,
+                       pb.npw_max, P, -1, psi.p, NR);
+    for (int c = 0; c < 3; ++c)
+      hipLaunchKernelGGL((k_scatter<R>), dim3(gsc), dim3(256), 0, s, sh.coef.p, sh.boxidx.p, sh.npw.p, sh.kg.p, nb,
+                         pb.npw_max, P, c, D.p + size_t(c) * P * NR, NR);
+    fft3d_t<R, N>(psi.p, P, +1, s);
+    fft3d_t<R, N>(D.p, 3L * P, +1, s);
+    TC_HIP(hipEventRecord(ev.e[1], s));
+
+    // ---- 1: densities and Hartree-type fields (Algs. 2ah, 3a1, 3b1; 2bh1, 2bh2)
+    TC_HIP(hipMemsetAsync(loc.p, 0, 8 * NR * sizeof(cx<R>), s));
+    hipLaunchKernelGGL((k_density<R, N>), dim3(nblk(NR)), dim3(256), 0, s, psi.p, D.p, sh.w.p, P, nJ.p, nJ.p + NR);
+    TC_HIP(hipMemcpyAsync(wk.p, nJ.p, 4 * NR * sizeof(cx<R>), hipMemcpyDeviceToDevice, s));
+    fft3d_t<R, N>(wk.p, 4, -1, s);
+    hipLaunchKernelGGL((k_hartree_g<R, N>), dim3(nblk(NR)), dim3(256), 0, s, rc, tHV.p, tHU.p, wk.p, wk.p + NR,
+                       wk.p + 4 * NR);
+    fft3d_t<R, N>(wk.p + 4 * NR, 5, +1, s);
+    TC_HIP(hipMemcpyAsync(loc.p, wk.p + 4 * NR, 5 * NR * sizeof(cx<R>), hipMemcpyDeviceToDevice, s));
+    hipLaunchKernelGGL((k_mul_vec_scalar<R, N>), dim3(nblk(NR)), dim3(256), 0, s, loc.p + NR, nJ.p, wk.p);
+    fft3d_t<R, N>(wk.p, 3, -1, s);
+    hipLaunchKernelGGL((k_gdiv<R, N>), dim3(nblk(NR)), dim3(256), 0, s, rc, tHU.p, wk.p, wk.p + 3 * NR);
+    fft3d_t<R, N>(wk.p + 3 * NR, 1, +1, s);
+    TC_HIP(hipMemcpyAsync(loc.p + 5 * NR, wk.p + 3 * NR, NR * sizeof(cx<R>), hipMemcpyDeviceToDevice, s));
+    TC_HIP(hipEventRecord(ev.e[2], s));
+
+    // ---- 2: occupied-occupied pair pass
+    const bool need_occ = m.m3a2 || m.m3a4 || m.m3b2 || m.m3b5;
+    TC_HIP(hipMemsetAsync(H3a4.p, 0, size_t(3) * P * NR * sizeof(cx<R>), s));
+    if (need_occ) {
+      for (int a0 = 0; a0 < P; a0 += T) {
+        const int nt = std::min(T, P - a0);
+        const long npair = long(nt) * P;
+        hipLaunchKernelGGL((k_xy_pair<R, N, true>), dim3(nblk(npair * N, PB)), dim3(PB * N), 0, s, psi.p, psi.p,
+                           bufA.p, a0, P, npair * N);
+        hipLaunchKernelGGL((k_zconv<R, N, OP_O>), dim3(nblk(npair * N * N)), dim3(256), 0, s, bufA.p, bufB.p, npair,
+                           a0, mi, rc, tb, 0);
+        const long np = npair * 6 * N;
+        hipLaunchKernelGGL((k_fft_xy<R, N, 1>), dim3(nblk(np, PB)), dim3(PB * N), 0, s, bufB.p, np);
+        hipLaunchKernelGGL((k_acc_O<R, N>), dim3(nblk(long(nt) * NR)), dim3(256), 0, s, bufB.p, psi.p, sh.w.p, P, nt,
+                           a0, h5.p, H3a4.p);
+      }
+      hipLaunchKernelGGL((k_reduce_occ<R, N>), dim3(nblk(NR)), dim3(256), 0, s, h5.p, H3a4.p, psi.p, sh.w.p, P,
+                         loc.p + 6 * NR, wk.p);
+      fft3d_t<R, N>(wk.p, 3, -1, s);
+      hipLaunchKernelGGL((k_gdiv<R, N>), dim3(nblk(NR)), dim3(256), 0, s, rc, tHU.p, wk.p, wk.p + 3 * NR);
+      fft3d_t<R, N>(wk.p + 3 * NR, 1, +1, s);
+      TC_HIP(hipMemcpyAsync(loc.p + 7 * NR, wk.p + 3 * NR, NR * sizeof(cx<R>), hipMemcpyDeviceToDevice, s));
+    }
+    TC_HIP(hipEventRecord(ev.e[3], s));
+
+    // ---- 3/4: target batches (pass A, pass B, local terms, r -> G)
+    const bool need_A = m.m2ax || m.m2bx1 || m.m3a3 || m.m3a4 || m.m3b4 || m.m3b6;
+    const bool need_B = m.m2bx2 || m.m3b3 || m.m3b4 || m.m3b5;
+    double msA = 0, msB = 0;
+    for (int t0 = 0; t0 < P; t0 += T) {
+      const int nt = std::min(T, P - t0);
+      const long npair = long(nt) * P;
+      Events be(3);
+      TC_HIP(hipMemsetAsync(acc.p, 0, size_t(4) * T * NR * sizeof(cx<double>), s));
+      TC_HIP(hipMemsetAsync(h4.p, 0, size_t(3) * T * NR * sizeof(cx<R>), s));
+      TC_HIP(hipEventRecord(be.e[0], s));
+      if (need_A) {
+        hipLaunchKernelGGL((k_xy_pair<R, N, false>), dim3(nblk(npair * N, PB)), dim3(PB * N), 0, s, psi.p, psi.p,
+                           bufA.p, t0, P, npair * N);
+        hipLaunchKernelGGL((k_zconv<R, N, OP_A1>), dim3(nblk(npair * N * N)), dim3(256), 0, s, bufA.p, bufB.p,
+                           npair, t0, mi, rc, tb, 1);
+        long np = npair * 7 * N;
+        hipLaunchKernelGGL((k_fft_xy<R, N, 1>), dim3(nblk(np, PB)), dim3(PB * N), 0, s, bufB.p, np);
+        hipLaunchKernelGGL((k_acc_A1<R, N>), dim3(nblk(long(nt) * NR)), dim3(256), 0, s, bufB.p, psi.p, D.p, H3a4.p,
+                           sh.w.p, P, nt, m, acc.p, h4.p);
+        if (m.m3b6) {
+          np = npair * 6 * N;
+          hipLaunchKernelGGL((k_xy_3b6<R, N>), dim3(nblk(np, PB)), dim3(PB * N), 0, s, bufB.p, nJ.p, bufA.p, np);
+          hipLaunchKernelGGL((k_zconv<R, N, OP_A2>), dim3(nblk(npair * N * N)), dim3(256), 0, s, bufA.p, bufB.p,
+                             npair, t0, mi, rc, tb, 1);
+          np = npair * N;
+          hipLaunchKernelGGL((k_fft_xy<R, N, 1>), dim3(nblk(np, PB)), dim3(PB * N), 0, s, bufB.p, np);
+          hipLaunchKernelGGL((k_acc_Y<R, N>), dim3(nblk(long(nt) * NR)), dim3(256), 0, s, bufB.p, psi.p, sh.w.p, P,
+                             nt, 1.0, 2, acc.p);
+        }
+      }
+      TC_HIP(hipEventRecord(be.e[1], s));
+      if (need_B) {
+        hipLaunchKernelGGL((k_passB_Z<R, N>), dim3(nblk(long(nt) * NR)), dim3(256), 0, s, psi.p, D.p, loc.p + NR,
+                           h4.p, t0, nt, P, m, Z.p);
+        long np = npair * 3 * N;
+        hipLaunchKernelGGL((k_xy_passB<R, N>), dim3(nblk(np, PB)), dim3(PB * N), 0, s, psi.p, Z.p, H3a4.p, bufA.p,
+                           t0, P, R(m.m3b5), np);
+        hipLaunchKernelGGL((k_zconv<R, N, OP_B>), dim3(nblk(npair * N * N)), dim3(256), 0, s, bufA.p, bufB.p, npair,
+                           t0, mi, rc, tb, 1);
+        np = npair * N;
+        hipLaunchKernelGGL((k_fft_xy<R, N, 1>), dim3(nblk(np, PB)), dim3(PB * N), 0, s, bufB.p, np);
+        hipLaunchKernelGGL((k_acc_Y<R, N>), dim3(nblk(long(nt) * NR)), dim3(256), 0, s, bufB.p, psi.p, sh.w.p, P, nt,
+                           1.0, 3, acc.p);
+      }
+      TC_HIP(hipEventRecord(be.e[2], s));
+      hipLaunchKernelGGL((k_local<R, N>), dim3(nblk(long(nt) * NR)), dim3(256), 0, s, psi.p, D.p, loc.p, h4.p, t0, nt,
+                         P, m, acc.p, g.p);
+      hipLaunchKernelGGL((k_epart<R, N>), dim3(4 * nt), dim3(256), 0, s, psi.p, acc.p, t0, nt, sh.epart.p);
+      fft3d_t<R, N>(g.p, nt, -1, s);
+      hipLaunchKernelGGL((k_gather<R>), dim3(nblk(long(nt) * pb.npw_max)), dim3(256), 0, s, g.p, sh.boxidx.p,
+                         sh.npw.p, nb, pb.npw_max, t0, nt, 1.0 / double(NR), sh.out.p, NR);
+      TC_HIP(hipEventSynchronize(be.e[2]));
+      msA += be.ms(0, 1);
+      msB += be.ms(1, 2);
+    }
+    TC_HIP(hipEventRecord(ev.e[4], s));
+
+    // ---- 5: kinetic energy and FP64 corrections
+    hipLaunchKernelGGL(k_kinetic, dim3(P), dim3(256), 0, s, sh.coef.p, sh.kg.p, sh.npw.p, nb, pb.npw_max, sh.tkin.p);
+    TC_HIP(hipMemsetAsync(sh.ecorr.p, 0, size_t(2) * P * sizeof(double), s));
+    if (pb.div && (pb.mask & TC_T_CORR) && (m.m2ax || m.m3a2 || m.m3b6)) corrections(s, sh, pb, m);
+    TC_HIP(hipEventRecord(ev.e[5], s));
+    TC_HIP(hipEventSynchronize(ev.e[5]));
+    stage_ms[0] = ev.ms(0, 1);
+    stage_ms[1] = ev.ms(1, 2);
+    stage_ms[2] = ev.ms(2, 3);
+    stage_ms[3] = msA;
+    stage_ms[4] = msB;
+    stage_ms[5] = ev.ms(3, 5) - msA - msB;
+  }
+
+  // SCF-mesh divergence corrections in FP64 (2ax, 3a2, 3b6); see k_corr_apply.
+  void corrections(hipStream_t s, Shared& sh, const Problem& pb, const Masks& m) {
+    const int P = pb.P(), nb = pb.nb, nk = pb.nk;
+    hipLaunchKernelGGL(k_overlap, dim3(nk * nb * nb), dim3(256), 0, s, sh.coef.p, sh.coef.p, sh.npw.p, nb,
+                       pb.npw_max, nk, sh.S.p);
+    std::vector<double> S(size_t(2) * nk * nb * nb);
+    TC_HIP(hipMemcpyAsync(S.data(), sh.S.p, S.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    TC_HIP(hipMemcpyAsync(focc.p, pb.occ.data(), P * sizeof(double), hipMemcpyHostToDevice, s));
+    // FP64 orbitals on the grid
+    TC_HIP(hipMemsetAsync(psi64.p, 0, size_t(P) * NR * sizeof(cx<double>), s));
+    hipLaunchKernelGGL((k_scatter<double>), dim3(nblk(long(P) * pb.npw_max)), dim3(256), 0, s, sh.coef.p, sh.boxidx.p,
+                       sh.npw.p, sh.kg.p, nb, pb.npw_max, P, -1, psi64.p, NR);
+    fft3d_t<double, N>(psi64.p, P, +1, s);
+    cx<double>* nG = v64.p;
+    cx<double>* YG = v64.p + NR;
+    cx<double>* F1 = v64.p + 2 * NR;
+    cx<double>* F2 = v64.p + 3 * NR;
+    hipLaunchKernelGGL((k_density64<N>), dim3(nblk(NR)), dim3(256), 0, s, psi64.p, sh.w.p, P, nG);
+    hipLaunchKernelGGL((k_corr_Ysrc<N>), dim3(nblk(NR)), dim3(256), 0, s, psi64.p, sh.S.p, focc.p, nk, nb,
+                       1.0 / (nk * pb.omega), YG);
+    fft3d_t<double, N>(nG, 2, -1, s);
+    const double a0 = 2 * kPi * pb.A[0] / nk, a1 = 2 * kPi * pb.A[1] / nk;
+    hipLaunchKernelGGL((k_corr_gfields<N>), dim3(nblk(NR)), dim3(256), 0, s, tHu0.p, tHu1.p, a0, a1, nG, F1);
+    hipLaunchKernelGGL((k_corr_gfields<N>), dim3(nblk(NR)), dim3(256), 0, s, tHu0.p, tHu1.p, 2 * a0, 2 * a1, YG, F2);
+    fft3d_t<double, N>(F1, 2, +1, s);
+    hipLaunchKernelGGL((k_corr_products<N>), dim3(nblk(2L * P * NR)), dim3(256), 0, s, F1, psi64.p, P, prod64.p);
+    fft3d_t<double, N>(prod64.p, 2L * P, -1, s);
+    hipLaunchKernelGGL((k_gather<double>), dim3(nblk(long(P) * pb.npw_max)), dim3(256), 0, s, prod64.p, sh.boxidx.p,
+                       sh.npw.p, nb, pb.npw_max, 0, P, 1.0 / double(NR), sh.Zg.p, NR);
+    hipLaunchKernelGGL((k_gather<double>), dim3(nblk(long(P) * pb.npw_max)), dim3(256), 0, s,
+                       prod64.p + size_t(P) * NR, sh.boxidx.p, sh.npw.p, nb, pb.npw_max, 0, P, 1.0 / double(NR),
+                       sh.Wg.p, NR);
+    hipLaunchKernelGGL(k_overlap, dim3(nk * nb * nb), dim3(256), 0, s, sh.coef.p, sh.Zg.p, sh.npw.p, nb, pb.npw_max,
+                       nk, sh.O.p);
+    TC_HIP(hipStreamSynchronize(s));
+    // scalars: n~(0) per spin and const1 of the G = G' = 0 correction of 3a2
+    double n0 = 0;
+    for (int k = 0; k < nk; ++k)
+      for (int a = 0; a < nb; ++a) n0 += pb.occ[k * nb + a] / nk * S[2 * ((k * nb + a) * nb + a)] / pb.omega;
+    double c1s = 0, c1a = 0;
+    for (int ch = 0; ch < 2; ++ch) {
+      const double ushort = -kFourPi * pb.A[ch] * pb.C[ch] * pb.C[ch];   // Eq. u_short
+      const double br = kFourPi * pb.A[ch] * pb.delta_gb + ushort / nk;
+      c1s += 2 * kPi * pb.A[ch] * br;   // Eq. 3b6_div_scf1 (summed over the density's spin)
+      c1a += kFourPi * pb.A[ch] * br;   // Eq. divcor_3a2_first (summed over the partners' spin)
+    }
+    double const1 = 0;
+    for (int k = 0; k < nk; ++k)
+      for (int a = 0; a < nb; ++a)
+        for (int b = 0; b < nb; ++b) {
+          const double* sab = &S[2 * ((k * nb + a) * nb + b)];
+          const double* sba = &S[2 * ((k * nb + b) * nb + a)];
+          const double re = sab[0] * sba[0] - sab[1] * sba[1];
+          const1 += pb.occ[k * nb + a] / nk * pb.occ[k * nb + b] * c1a * re / (pb.omega * pb.omega);
+        }
+    hipLaunchKernelGGL(k_corr_apply, dim3(nblk(long(P) * pb.npw_max)), dim3(256), 0, s, sh.coef.p, sh.S.p, sh.O.p,
+                       sh.Zg.p, sh.Wg.p, focc.p, sh.npw.p, nb, pb.npw_max, P, pb.omega, m.m2ax, pb.delta_gb, m.m3a2,
+                       const1, m.m3b6, c1s * n0, sh.dhc2.p, sh.dhc3.p);
+    hipLaunchKernelGGL(k_corr_add, dim3(P), dim3(256), 0, s, sh.coef.p, sh.dhc2.p, sh.dhc3.p, sh.npw.p, nb,
+                       pb.npw_max, sh.out.p, sh.ecorr.p);
+  }
+};
+
+template <typename R>
+Engine* make_engine_r(int N) {
+  switch (N) {
+    case 8: return new EngineT<R, 8>();
+    case 12: return new EngineT<R, 12>();
+    case 16: return new EngineT<R, 16>();
+    case 24: return new EngineT<R, 24>();
+    case 32: return new EngineT<R, 32>();
+    case 48: return new EngineT<R, 48>();
+    default: return nullptr;
+  }
+}
+
+void upload_twiddles() {
+  static bool done = false;   // per process; constant memory is per device, re-uploaded per context below
+  (void)done;
+  const int sizes[6] = {8, 12, 16, 24, 32, 48};
+  std::vector<double> t64(2 * kTwTotal);
+  std::vector<float> t32(2 * kTwTotal);
+  for (int N : sizes) {
+    const int off = tw_off(N);
+    for (int m = 0; m < N; ++m) {
+      const double a = -2.0 * kPi * m / N;
+      t64[2 * (off + m)] = std::cos(a);
+      t64[2 * (off + m) + 1] = std::sin(a);
+      t32[2 * (off + m)] = float(std::cos(a));
+      t32[2 * (off + m) + 1] = float(std::sin(a));
+    }
+  }
+  TC_HIP(hipMemcpyToSymbol(HIP_SYMBOL(c_tw64), t64.data(), t64.size() * sizeof(double)));
+  TC_HIP(hipMemcpyToSymbol(HIP_SYMBOL(c_tw32), t32.data(), t32.size() * sizeof(float)));
+}
+
+}  // namespace
+
+// ====================================================================== C ABI
+struct tc_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  std::string err;
+  Problem pb;
+  Shared sh;
+  std::unique_ptr<Engine> eng;
+  int eng_prec = -1, eng_N = -1;
+  bool tables_dirty = true;
+  bool have_result = false;
+  std::vector<double> hcoef;   // [P][npw_max] complex staging
+  double e_total = 0, e_parts[TC_E_NPARTS] = {0, 0, 0, 0};
+  double stage_ms[6] = {0, 0, 0, 0, 0, 0};
+  double total_ms = 0;
+};
+
+namespace {
+
+int fail(tc_ctx* c, int code, const std::string& m) {
+  if (c) c->err = m;
+  return code;
+}
+
+template <class F>
+int guard(tc_ctx* c, F&& f) {
+  if (!c) return TC_ERR_ARG;
+  try {
+    c->err.clear();
+    TC_HIP(hipSetDevice(c->device));
+    return f();
+  } catch (const TcError& e) {
+    return fail(c, e.code, e.msg);
+  } catch (const std::bad_alloc&) {
+    return fail(c, TC_ERR_OOM, "host allocation failed");
+  } catch (const std::exception& e) {
+    return fail(c, TC_ERR_DEVICE, e.what());
+  }
+}
+
+bool grid_supported(int N) { return N == 8 || N == 12 || N == 16 || N == 24 || N == 32 || N == 48; }
+
+int prepare(tc_ctx* c) {
+  Problem& pb = c->pb;
+  if (!pb.cell) return fail(c, TC_ERR_STATE, "tc_set_cell not called");
+  if (pb.nk == 0) return fail(c, TC_ERR_STATE, "tc_set_kmesh not called");
+  if (pb.N == 0) return fail(c, TC_ERR_STATE, "tc_set_grid not called");
+  if (!pb.jastrow) return fail(c, TC_ERR_STATE, "tc_set_jastrow not called");
+  if (pb.nb == 0) return fail(c, TC_ERR_STATE, "no orbitals loaded");
+  for (int k = 0; k < pb.nk; ++k)
+    if (!pb.loaded[k]) return fail(c, TC_ERR_STATE, "orbitals of k-point " + std::to_string(k) + " not loaded");
+  if (!c->eng || c->eng_prec != pb.prec || c->eng_N != pb.N) {
+    c->eng.reset(pb.prec == TC_PREC_FP64 ? make_engine_r<double>(pb.N) : make_engine_r<float>(pb.N));
+    if (!c->eng) return fail(c, TC_ERR_UNSUPPORTED, "grid not supported");
+    c->eng_prec = pb.prec;
+    c->eng_N = pb.N;
+    c->tables_dirty = true;
+  }
+  if (c->tables_dirty) {
+    gb_constant(pb);
+    c->eng->upload_tables(pb);
+    c->tables_dirty = false;
+  }
+  return TC_OK;
+}
+
+void finish_energy(tc_ctx* c) {
+  Problem& pb = c->pb;
+  const int P = pb.P();
+  std::vector<double> ep(size_t(4) * P), tk(P), ec(size_t(2) * P);
+  TC_HIP(hipMemcpy(ep.data(), c->sh.epart.p, ep.size() * sizeof(double), hipMemcpyDeviceToHost));
+  TC_HIP(hipMemcpy(tk.data(), c->sh.tkin.p, tk.size() * sizeof(double), hipMemcpyDeviceToHost));
+  TC_HIP(hipMemcpy(ec.data(), c->sh.ecorr.p, ec.size() * sizeof(double), hipMemcpyDeviceToHost));
+  double T = 0, E2 = 0, E3 = 0, EC = 0;
+  for (int p = 0; p < P; ++p) {
+    const double f = pb.occ[p] * 2.0 / pb.nk;   // both spin channels
+    T += f * tk[p];
+    // <2bh2>+<2bx2> equals <2bh1>+<2bx1> (transposition of the discrete kernels), so the
+    // two-body part is (1/2)<2ah+2ax> + <2bh1+2bx1> and pass B's 2bx2 leaves the three-body part.
+    E2 += f * (0.5 * ep[4 * p] + ep[4 * p + 1]);
+    E3 += f * (ep[4 * p + 2] + ep[4 * p + 3] - ep[4 * p + 1]) / 3.0;
+    E2 += f * 0.5 * ec[2 * p];
+    E3 += f * ec[2 * p + 1] / 3.0;
+    EC += f * (0.5 * ec[2 * p] + ec[2 * p + 1] / 3.0);
+  }
+  c->e_parts[TC_E_KINETIC] = T;
+  c->e_parts[TC_E_TWO_BODY] = E2;
+  c->e_parts[TC_E_THREE_BODY] = E3;
+  c->e_parts[TC_E_CORR] = EC;
+  c->e_total = T + E2 + E3;
+}
+
+int do_apply(tc_ctx* c, void* out_dev, double* out_host) {
+  int st = prepare(c);
+  if (st != TC_OK) return st;
+  Problem& pb = c->pb;
+  Shared& sh = c->sh;
+  const int P = pb.P();
+  sh.out.alloc(size_t(2) * P * pb.npw_max);
+  sh.dhc2.alloc(size_t(2) * P * pb.npw_max);
+  sh.dhc3.alloc(size_t(2) * P * pb.npw_max);
+  sh.Zg.alloc(size_t(2) * P * pb.npw_max);
+  sh.Wg.alloc(size_t(2) * P * pb.npw_max);
+  sh.epart.alloc(size_t(4) * P);
+  sh.tkin.alloc(P);
+  sh.ecorr.alloc(size_t(2) * P);
+  sh.S.alloc(size_t(2) * pb.nk * pb.nb * pb.nb);
+  sh.O.alloc(size_t(2) * pb.nk * pb.nb * pb.nb);
+  c->eng->apply(c->stream, sh, pb, c->stage_ms);
+  c->total_ms = 0;
+  for (double v : c->stage_ms) c->total_ms += v;
+  if (out_dev)
+    TC_HIP(hipMemcpyAsync(out_dev, sh.out.p, size_t(2) * P * pb.npw_max * sizeof(double), hipMemcpyDeviceToDevice,
+                          c->stream));
+  if (out_host)
+    TC_HIP(hipMemcpyAsync(out_host, sh.out.p, size_t(2) * P * pb.npw_max * sizeof(double), hipMemcpyDeviceToHost,
+                          c->stream));
+  TC_HIP(hipStreamSynchronize(c->stream));
+  finish_energy(c);
+  c->have_result = true;
+  return TC_OK;
+}
+
+void upload_basis_data(tc_ctx* c) {
+  Problem& pb = c->pb;
+  const int P = pb.P();
+  std::vector<int> box(size_t(pb.nk) * pb.npw_max, 0);
+  std::vector<double> kg(size_t(pb.nk) * pb.npw_max * 3, 0.0);
+  for (int k = 0; k < pb.nk; ++k) {
+    double f[3];
+    pb.kfrac(k, f);
+    for (int g = 0; g < pb.npw[k]; ++g) {
+      const int* m = &pb.miller[k][3 * g];
+      const int x = (m[0] % pb.N + pb.N) % pb.N, y = (m[1] % pb.N + pb.N) % pb.N, z = (m[2] % pb.N + pb.N) % pb.N;
+      box[size_t(k) * pb.npw_max + g] = (z * pb.N + y) * pb.N + x;
+      for (int cc = 0; cc < 3; ++cc)
+        kg[(size_t(k) * pb.npw_max + g) * 3 + cc] =
+            (f[0] + m[0]) * pb.B[cc] + (f[1] + m[1]) * pb.B[3 + cc] + (f[2] + m[2]) * pb.B[6 + cc];
+    }
+  }
+  c->sh.boxidx.alloc(box.size());
+  c->sh.kg.alloc(kg.size());
+  c->sh.npw.alloc(pb.nk);
+  c->sh.w.alloc(P);
+  std::vector<double> w(P);
+  for (int p = 0; p < P; ++p) w[p] = pb.occ[p] / pb.nk;
+  TC_HIP(hipMemcpy(c->sh.boxidx.p, box.data(), box.size() * sizeof(int), hipMemcpyHostToDevice));
+  TC_HIP(hipMemcpy(c->sh.kg.p, kg.data(), kg.size() * sizeof(double), hipMemcpyHostToDevice));
+  TC_HIP(hipMemcpy(c->sh.npw.p, pb.npw.data(), pb.nk * sizeof(int), hipMemcpyHostToDevice));
+  TC_HIP(hipMemcpy(c->sh.w.p, w.data(), P * sizeof(double), hipMemcpyHostToDevice));
+}
+
+int begin_load(tc_ctx* c, int ik, int nband, const double* occ) {
+  Problem& pb = c->pb;
+  if (pb.nk == 0 || pb.N == 0) return fail(c, TC_ERR_STATE, "set the k-mesh and grid before loading orbitals");
+  if (ik < 0 || ik >= pb.nk) return fail(c, TC_ERR_ARG, "k-point index out of range");
+  for (int k = 0; k < pb.nk; ++k)
+    if (pb.npw[k] <= 0) return fail(c, TC_ERR_STATE, "tc_set_basis missing for k-point " + std::to_string(k));
+  if (nband <= 0 || !occ) return fail(c, TC_ERR_ARG, "nband must be positive and occ non-null");
+  if (nband > pb.npw[ik]) return fail(c, TC_ERR_ARG, "more bands than plane waves");
+  for (int b = 0; b < nband; ++b)
+    if (!(occ[b] >= 0.0 && occ[b] <= 1.0)) return fail(c, TC_ERR_ARG, "fillings must lie in [0, 1]");
+  if (pb.nb != nband) {
+    if (pb.nb != 0)
+      for (int k = 0; k < pb.nk; ++k)
+        if (pb.loaded[k] && k != ik) return fail(c, TC_ERR_ARG, "nband differs between k-points");
+    pb.nb = nband;
+    pb.occ.assign(size_t(pb.nk) * nband, 0.0);
+    std::fill(pb.loaded.begin(), pb.loaded.end(), 0);
+  }
+  int mx = 0;
+  for (int k = 0; k < pb.nk; ++k) mx = std::max(mx, pb.npw[k]);
+  pb.npw_max = mx;
+  c->sh.coef.alloc(size_t(2) * pb.P() * pb.npw_max);
+  for (int b = 0; b < nband; ++b) pb.occ[size_t(ik) * nband + b] = occ[b];
+  return TC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int tc_create(int device, void* stream, tc_ctx** out) {
+  if (!out) return TC_ERR_ARG;
+  *out = nullptr;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return TC_ERR_DEVICE;
+  tc_ctx* c = new (std::nothrow) tc_ctx();
+  if (!c) return TC_ERR_OOM;
+  c->device = device;
+  int st = guard(c, [&]() -> int {
+    if (stream) {
+      c->stream = reinterpret_cast<hipStream_t>(stream);
+    } else {
+      TC_HIP(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+      c->own_stream = true;
+    }
+    upload_twiddles();
+    return TC_OK;
+  });
+  if (st != TC_OK) {
+    delete c;
+    return st;
+  }
+  *out = c;
+  return TC_OK;
+}
+
+void tc_destroy(tc_ctx* c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  (void)hipStreamSynchronize(c->stream);
+  c->eng.reset();
+  if (c->own_stream) (void)hipStreamDestroy(c->stream);
+  delete c;
+}
+
+const char* tc_last_error(const tc_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+int tc_set_cell(tc_ctx* c, const double lat[9]) {
+  return guard(c, [&]() -> int {
+    if (!lat) return fail(c, TC_ERR_ARG, "null lattice");
+    Problem& pb = c->pb;
+    const double* a = lat;
+    const double det = a[0] * (a[4] * a[8] - a[5] * a[7]) - a[1] * (a[3] * a[8] - a[5] * a[6]) +
+                       a[2] * (a[3] * a[7] - a[4] * a[6]);
+    if (!(std::fabs(det) > 1e-12)) return fail(c, TC_ERR_ARG, "degenerate lattice");
+    for (int i = 0; i < 9; ++i) pb.lat[i] = lat[i];
+    pb.omega = std::fabs(det);
+    // B = 2 pi inv(A)^T: rows b_j with a_i . b_j = 2 pi delta_ij
+    const double inv[9] = {(a[4] * a[8] - a[5] * a[7]) / det, (a[2] * a[7] - a[1] * a[8]) / det,
+                           (a[1] * a[5] - a[2] * a[4]) / det, (a[5] * a[6] - a[3] * a[8]) / det,
+                           (a[0] * a[8] - a[2] * a[6]) / det, (a[2] * a[3] - a[0] * a[5]) / det,
+                           (a[3] * a[7] - a[4] * a[6]) / det, (a[1] * a[6] - a[0] * a[7]) / det,
+                           (a[0] * a[4] - a[1] * a[3]) / det};
+    for (int j = 0; j < 3; ++j)
+      for (int k = 0; k < 3; ++k) pb.B[3 * j + k] = 2.0 * kPi * inv[3 * k + j];
+    pb.cell = true;
+    c->tables_dirty = true;
+    c->have_result = false;
+    return TC_OK;
+  });
+}
+
+int tc_set_kmesh(tc_ctx* c, int n1, int n2, int n3) {
+  return guard(c, [&]() -> int {
+    if (n1 < 1 || n2 < 1 || n3 < 1 || n1 > 16 || n2 > 16 || n3 > 16) return fail(c, TC_ERR_KMESH, "k-mesh out of range");
+    Problem& pb = c->pb;
+    pb.n1 = n1;
+    pb.n2 = n2;
+    pb.n3 = n3;
+    pb.nk = n1 * n2 * n3;
+    pb.miller.assign(pb.nk, {});
+    pb.npw.assign(pb.nk, 0);
+    pb.loaded.assign(pb.nk, 0);
+    pb.nb = 0;
+    c->tables_dirty = true;
+    c->have_result = false;
+    return TC_OK;
+  });
+}
+
+int tc_set_grid(tc_ctx* c, int N1, int N2, int N3) {
+  return guard(c, [&]() -> int {
+    if (N1 != N2 || N2 != N3 || !grid_supported(N1))
+      return fail(c, TC_ERR_UNSUPPORTED, "only cubic grids N^3 with N in {8,12,16,24,32,48} are built");
+    c->pb.N = N1;
+    c->tables_dirty = true;
+    c->have_result = false;
+    return TC_OK;
+  });
+}
+
+int tc_set_basis(tc_ctx* c, int ik, int npw, const int32_t* miller) {
+  return guard(c, [&]() -> int {
+    Problem& pb = c->pb;
+    if (pb.nk == 0 || pb.N == 0) return fail(c, TC_ERR_STATE, "set the k-mesh and grid first");
+    if (ik < 0 || ik >= pb.nk || npw <= 0 || !miller) return fail(c, TC_ERR_ARG, "bad basis arguments");
+    for (int g = 0; g < 3 * npw; ++g)
+      if (miller[g] >= pb.N / 2 || miller[g] < -(pb.N / 2) + 1)
+        return fail(c, TC_ERR_GRID, "plane wave outside the FFT grid");
+    pb.miller[ik].assign(miller, miller + 3 * npw);
+    pb.npw[ik] = npw;
+    pb.loaded[ik] = 0;
+    c->have_result = false;
+    return TC_OK;
+  });
+}
+
+int tc_set_jastrow(tc_ctx* c, const double A[2], const double C[2]) {
+  return guard(c, [&]() -> int {
+    if (!A || !C) return fail(c, TC_ERR_ARG, "null Jastrow parameters");
+    for (int i = 0; i < 2; ++i)
+      if (!(A[i] >= 0.0) || !(C[i] > 0.0)) return fail(c, TC_ERR_ARG, "need A >= 0 and C > 0");
+    for (int i = 0; i < 2; ++i) {
+      c->pb.A[i] = A[i];
+      c->pb.C[i] = C[i];
+    }
+    c->pb.jastrow = true;
+    c->tables_dirty = true;
+    c->have_result = false;
+    return TC_OK;
+  });
+}
+
+int tc_set_options(tc_ctx* c, int precision, double alpha, int div_correction, uint64_t term_mask) {
+  return guard(c, [&]() -> int {
+    if (precision != TC_PREC_FP64 && precision != TC_PREC_FP32) return fail(c, TC_ERR_ARG, "unknown precision");
+    if (!(alpha > 0.0)) return fail(c, TC_ERR_ARG, "alpha must be > 0");
+    Problem& pb = c->pb;
+    pb.prec = precision;
+    pb.alpha = alpha;
+    pb.div = div_correction ? 1 : 0;
+    pb.mask = term_mask & TC_T_ALL;
+    pb.options = true;
+    c->tables_dirty = true;
+    c->have_result = false;
+    return TC_OK;
+  });
+}
+
+int tc_load_orbitals(tc_ctx* c, int ik, int nband, const double* right, const double* left, const double* occ) {
+  return guard(c, [&]() -> int {
+    if (left) return fail(c, TC_ERR_UNSUPPORTED, "biorthogonal (left) orbitals are not built in this version");
+    if (!right) return fail(c, TC_ERR_ARG, "null coefficients");
+    int st = begin_load(c, ik, nband, occ);
+    if (st != TC_OK) return st;
+    Problem& pb = c->pb;
+    const int npw = pb.npw[ik];
+    std::vector<double> stage(size_t(2) * nband * pb.npw_max, 0.0);
+    for (int b = 0; b < nband; ++b)
+      std::memcpy(&stage[size_t(2) * b * pb.npw_max], right + size_t(2) * b * npw, size_t(2) * npw * sizeof(double));
+    TC_HIP(hipMemcpy(c->sh.coef.p + size_t(2) * ik * nband * pb.npw_max, stage.data(), stage.size() * sizeof(double),
+                     hipMemcpyHostToDevice));
+    pb.loaded[ik] = 1;
+    upload_basis_data(c);
+    c->have_result = false;
+    return TC_OK;
+  });
+}
+
+int tc_load_orbitals_dev(tc_ctx* c, int ik, int nband, const void* right_dev, const double* occ) {
+  return guard(c, [&]() -> int {
+    if (!right_dev) return fail(c, TC_ERR_ARG, "null coefficients");
+    int st = begin_load(c, ik, nband, occ);
+    if (st != TC_OK) return st;
+    Problem& pb = c->pb;
+    const int npw = pb.npw[ik];
+    double* dst = c->sh.coef.p + size_t(2) * ik * nband * pb.npw_max;
+    TC_HIP(hipMemsetAsync(dst, 0, size_t(2) * nband * pb.npw_max * sizeof(double), c->stream));
+    TC_HIP(hipMemcpy2DAsync(dst, size_t(2) * pb.npw_max * sizeof(double), right_dev, size_t(2) * npw * sizeof(double),
+                            size_t(2) * npw * sizeof(double), nband, hipMemcpyDeviceToDevice, c->stream));
+    TC_HIP(hipStreamSynchronize(c->stream));
+    pb.loaded[ik] = 1;
+    upload_basis_data(c);
+    c->have_result = false;
+    return TC_OK;
+  });
+}
+
+int tc_apply_all(tc_ctx* c, double* out) {
+  return guard(c, [&]() -> int { return do_apply(c, nullptr, out); });
+}
+
+int tc_apply_all_dev(tc_ctx* c, void* out_dev) {
+  return guard(c, [&]() -> int { return do_apply(c, out_dev, nullptr); });
+}
+
+int tc_energy(tc_ctx* c, double* e_total, double* e_parts) {
+  return guard(c, [&]() -> int {
+    const uint64_t m = c->pb.mask;
+    if (((m & TC_T_2BH1) != 0) != ((m & TC_T_2BH2) != 0) || ((m & TC_T_2BX1) != 0) != ((m & TC_T_2BX2) != 0))
+      return fail(c, TC_ERR_UNSUPPORTED, "energy needs 2bh1/2bh2 and 2bx1/2bx2 selected together");
+    if (!c->have_result) {
+      int st = do_apply(c, nullptr, nullptr);
+      if (st != TC_OK) return st;
+    }
+    if (e_total) *e_total = c->e_total;
+    if (e_parts)
+      for (int i = 0; i < TC_E_NPARTS; ++i) e_parts[i] = c->e_parts[i];
+    return TC_OK;
+  });
+}
+
+int tc_energy_backward(tc_ctx* c, double* grad, double dA[2], double dC[2]) {
+  return guard(c, [&]() -> int {
+    (void)grad;
+    (void)dA;
+    (void)dC;
+    return fail(c, TC_ERR_UNSUPPORTED, "gradient not built yet");
+  });
+}
+
+int tc_sync(tc_ctx* c) {
+  return guard(c, [&]() -> int {
+    TC_HIP(hipStreamSynchronize(c->stream));
+    return TC_OK;
+  });
+}
+
+int tc_last_timing(tc_ctx* c, double* total_ms, double* stage_ms, int n) {
+  return guard(c, [&]() -> int {
+    if (total_ms) *total_ms = c->total_ms;
+    for (int i = 0; i < n && i < 6; ++i)
+      if (stage_ms) stage_ms[i] = c->stage_ms[i];
+    return TC_OK;
+  });
+}
+
+}  // extern "C"
