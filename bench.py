@@ -1,0 +1,214 @@
+"""Benchmark of the transcorrelated-operator hot path on one MI355X.
+
+A step is one full application of the two- and three-body TC operator (all
+terms, SCF-mesh divergence corrections, energy) to every occupied orbital of
+the diamond-lattice silicon-like workload: fcc a = 10.26 bohr, 4x4x4 Gamma-centred
+k-mesh, 4 occupied bands, ~300 plane waves per k, 24^3 FFT grid (65,536
+same-spin orbital pairs).  The orbital coefficients are resident in HBM before
+the timed region; each step runs G->r, the Hartree-type fields, the
+occupied-occupied pass, passes A and B, r->G, the FP64 corrections and the
+energy reductions.
+
+Prints one JSON line (rank 0).  Metric: orbital-pair TC applications per
+second = N_pairs / (seconds per step).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, HERE)
+
+METRIC = "orbital-pair TC applications/sec + TC energy error vs FP64 oracle (FP32 vs FP64)"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def make_op(w, precision, stream):
+    import torch
+    import paper_2302_07420_amd as tc
+
+    op = tc.TCOperator(0, stream)
+    op.set_cell(w.lattice)
+    op.set_kmesh(*w.kmesh)
+    op.set_grid(*w.grid)
+    for ik, m in enumerate(w.miller):
+        op.set_basis(ik, m)
+    op.set_jastrow(w.A, w.C)
+    op.set_options(precision, w.alpha, True, tc.TERM_ALL)
+    # coefficients resident in HBM (torch owns the memory)
+    keep = []
+    for ik, c in enumerate(w.right):
+        t = torch.from_numpy(c).to("cuda")
+        keep.append(t)
+        op.load_orbitals_dev(ik, t.data_ptr(), c.shape[0], w.occ[ik])
+    torch.cuda.synchronize()
+    return op, keep
+
+
+def time_steps(op, out, steps, warmup, profile=False):
+    import torch
+
+    for _ in range(warmup):
+        op.apply_dev(out.data_ptr())
+        op.energy()
+    torch.cuda.synchronize()
+    if profile:
+        op.kernel_stats(reset=True)
+        op.set_profiling(True)
+    stream = torch.cuda.current_stream()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter()
+    t0.record(stream)
+    energies = []
+    for _ in range(steps):
+        op.apply_dev(out.data_ptr())
+        energies.append(op.energy())
+    t1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall
+    ms = t0.elapsed_time(t1) / steps
+    stats = op.kernel_stats(reset=True) if profile else None
+    if profile:
+        op.set_profiling(False)
+    return ms, wall / steps * 1e3, energies, stats
+
+
+def cpu_baseline(budget_s: float):
+    """The FP64 oracle as it stands on a bounded sample of the workload (same cell,
+    grid, bands and Jastrow; 2x2x2 k-mesh = 32 orbitals per spin, 1024 same-spin pairs)."""
+    import torch
+    import tcinputs as T
+    from oracle.fftroute import Problem
+
+    cores = len(os.sched_getaffinity(0))
+    torch.set_num_threads(cores)
+    w = T.fcc_si(kmesh=(2, 2, 2))
+    t = time.perf_counter()
+    with torch.no_grad():
+        pr = Problem(w)
+        E = float(pr.energy())
+    dt = time.perf_counter() - t
+    npairs = w.npairs
+    return {
+        "value": npairs / dt,
+        "unit": "orbital-pair TC applications/s",
+        "cores": torch.get_num_threads(),
+        "kind": "oracle",
+        "sample": f"config-2 cell, 24^3 grid, 4 bands, 2x2x2 k-mesh ({npairs} same-spin pairs, all terms, "
+                  f"both spins, energy {E:.10f} Ha); {dt:.1f} s",
+        "seconds": dt,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 GPU path")
+    ap.add_argument("--config", type=int, default=2, help="workload: 1, 2 (default), 3 or 4")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only: this build has no multi-GPU path (asked for --gpus {args.gpus})",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import tcinputs as T
+    import paper_2302_07420_amd as tc
+
+    w = T.config(args.config)
+    log(f"workload {w.name}: nk={w.nk} nb={w.nband} grid={w.grid} pairs={w.npairs}")
+    side = torch.cuda.Stream()          # default priority; the library enqueues on this stream
+    torch.cuda.set_stream(side)
+    stream = side.cuda_stream
+    out = torch.empty((w.nk, w.nband, max(m.shape[0] for m in w.miller)), dtype=torch.complex128, device="cuda")
+
+    op32, keep32 = make_op(w, tc.TC_PREC_FP32, stream)
+    ms32, wall32, e32, stats = time_steps(op32, out, args.steps, args.warmup, profile=True)
+    E32 = e32[-1][0]
+    tot, stages = op32.timing()
+    log(f"fp32: {ms32:.2f} ms/step (wall {wall32:.2f}), E = {E32:.12f}")
+
+    fp64 = None
+    if not args.no_fp64:
+        op64, keep64 = make_op(w, tc.TC_PREC_FP64, stream)
+        ms64, wall64, e64, _ = time_steps(op64, out, max(1, min(args.steps, 2)), 1)
+        E64 = e64[-1][0]
+        fp64 = {"value": w.npairs / (ms64 / 1e3), "ms_per_step": ms64, "energy_Ha": E64}
+        log(f"fp64: {ms64:.2f} ms/step, E = {E64:.12f}")
+        op64.close()
+        del keep64
+
+    # dominant kernel and its roofline (algorithmic bytes / event-timed duration)
+    dom = max(stats.items(), key=lambda kv: kv[1]["ms"])
+    name, st = dom
+    avg_ms = st["ms"] / max(1, st["launches"])
+    avg_bytes = st["bytes"] / max(1, st["launches"])
+    achieved = avg_bytes / (avg_ms * 1e-3) / 1e9
+    total_kernel_ms = sum(v["ms"] for v in stats.values()) / args.steps
+    roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+            "traffic": None, "kernel": name.replace("<R,N", "<float,%d" % w.grid[0]),
+            "avg_launch_ms": avg_ms, "algorithmic_bytes_per_launch": avg_bytes,
+            "launches_per_step": st["launches"] / args.steps}
+    per_kernel = {k: {"ms_per_step": v["ms"] / args.steps,
+                      "GBps": (v["bytes"] / (v["ms"] * 1e-3) / 1e9) if v["ms"] > 0 and v["bytes"] > 0 else None}
+                  for k, v in stats.items() if v["ms"] > 0}
+
+    cpu = None
+    if not args.no_cpu:
+        try:
+            cpu = cpu_baseline(30.0)
+            log(f"cpu oracle: {cpu['value']:.3f} pairs/s on {cpu['cores']} threads ({cpu['seconds']:.1f} s)")
+        except Exception as e:  # the baseline is reported, never required
+            log(f"cpu baseline failed: {e!r}")
+
+    res = {
+        "metric": METRIC,
+        "value": w.npairs / (ms32 / 1e3),
+        "unit": "orbital-pair TC applications/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms32,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{w.name}: fcc a=10.26 bohr silicon-like cell, {w.kmesh[0]}x{w.kmesh[1]}x{w.kmesh[2]} "
+                        f"Gamma-centred k-mesh, {w.nband} occupied bands, "
+                        f"{sum(m.shape[0] for m in w.miller) / w.nk:.1f} plane waves/k, {w.grid[0]}^3 grid, "
+                        f"all two- and three-body TC terms + SCF-mesh GB corrections + energy",
+            "n_pairs": w.npairs,
+            "precision": "fp32 FFTs / pair products / kernel multiplies; fp64 partner sums, corrections, energies",
+        },
+        "energy_Ha": E32,
+        "energy_rel_err_fp32_vs_fp64": (abs(E32 - fp64["energy_Ha"]) / abs(fp64["energy_Ha"])) if fp64 else None,
+        "fp64_gpu": fp64,
+        "speedup_fp32_vs_fp64_gpu": (w.npairs / (ms32 / 1e3)) / fp64["value"] if fp64 else None,
+        "stages_ms": dict(zip(tc.STAGES, stages)),
+        "kernels_ms_per_step": per_kernel,
+        "kernel_ms_per_step_total": total_kernel_ms,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(res), flush=True)
+    op32.close()
+
+
+if __name__ == "__main__":
+    main()

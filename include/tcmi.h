@@ -158,6 +158,45 @@ int tc_sync(tc_ctx* ctx);
  * 3 pass A, 4 pass B, 5 r->G and FP64 corrections). */
 int tc_last_timing(tc_ctx* ctx, double* total_ms, double* stage_ms, int n);
 
+/* Number of target orbitals processed per pass-A/B batch (and occupied partners per
+ * batch of the occupied-occupied pass).  0 (default) sizes batches to ~8 GiB of pair
+ * buffers.  Results do not depend on it; tests use small values to cover batching. */
+int tc_set_batch(tc_ctx* ctx, int targets_per_batch);
+
+/* Kernels timed by tc_kernel_stats (device time between HIP events recorded on the
+ * context's stream around every launch).  Each index names one kernel symbol of the
+ * library (working precision R, grid length N), as listed by a kernel trace. */
+enum {
+  TC_K_SCATTER = 0,     /* k_scatter: coefficients into the FFT box                     */
+  TC_K_FFT_XY_FWD = 1,  /* k_fft_xy<R,N,-1>: forward xy-plane transforms                */
+  TC_K_FFT_XY_INV = 2,  /* k_fft_xy<R,N,+1>: inverse xy-plane transforms                */
+  TC_K_FFT_Z_FWD = 3,   /* k_fft_z<R,N,-1>                                               */
+  TC_K_FFT_Z_INV = 4,   /* k_fft_z<R,N,+1>                                               */
+  TC_K_XY_PAIR_OCC = 5, /* k_xy_pair<R,N,true>: occupied-occupied pair densities, fwd xy */
+  TC_K_XY_PAIR_TGT = 6, /* k_xy_pair<R,N,false>: target-partner pair densities, fwd xy  */
+  TC_K_XY_3B6 = 7,      /* k_xy_3b6: 3b6 sources X^U n, fwd xy                          */
+  TC_K_XY_PASSB = 8,    /* k_xy_passB: pass-B sources, fwd xy                           */
+  TC_K_ZCONV_OCC = 9,   /* k_zconv<R,N,OP_O>                                            */
+  TC_K_ZCONV_A1 = 10,   /* k_zconv<R,N,OP_A1>                                           */
+  TC_K_ZCONV_A2 = 11,   /* k_zconv<R,N,OP_A2>                                           */
+  TC_K_ZCONV_B = 12,    /* k_zconv<R,N,OP_B>                                            */
+  TC_K_ACC_OCC = 13,    /* k_acc_O: FP64 partner sums of the occupied-occupied pass     */
+  TC_K_ACC_A1 = 14,     /* k_acc_A1: FP64 partner sums of pass A                        */
+  TC_K_ACC_Y = 15,      /* k_acc_Y: FP64 partner sums of the 3b6 chain and pass B       */
+  TC_K_OTHER = 16,      /* densities, Hartree-type fields, local terms, gathers          */
+  TC_K_CORR = 17,       /* FP64 corrections, overlaps and kinetic energy                 */
+  TC_K_NKERNEL = 18
+};
+
+/* Enable (1) or disable (0) per-kernel event timing for later applications. */
+int tc_set_profiling(tc_ctx* ctx, int on);
+
+/* Accumulated device milliseconds, launch counts and algorithmic bytes (reads +
+ * writes of the fields each launch must touch at least once) per kernel since
+ * profiling was enabled; each array has TC_K_NKERNEL entries (NULL allowed).
+ * reset != 0 clears the accumulators after reading. */
+int tc_kernel_stats(tc_ctx* ctx, double* ms, double* launches, double* bytes, int reset);
+
 #ifdef __cplusplus
 }
 #endif

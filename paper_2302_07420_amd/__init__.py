@@ -25,6 +25,12 @@ TERM_BITS = {
 }
 TERM_ALL = (1 << 17) - 1
 E_PARTS = ("kinetic", "two_body", "three_body", "corrections")
+# kernel index -> symbol stem (working precision R, grid length N), see TC_K_* in include/tcmi.h
+KERNELS = ("k_scatter", "k_fft_xy<R,N,-1>", "k_fft_xy<R,N,1>", "k_fft_z<R,N,-1>", "k_fft_z<R,N,1>",
+           "k_xy_pair<R,N,true>", "k_xy_pair<R,N,false>", "k_xy_3b6", "k_xy_passB", "k_zconv<R,N,OP_O>",
+           "k_zconv<R,N,OP_A1>", "k_zconv<R,N,OP_A2>", "k_zconv<R,N,OP_B>", "k_acc_O", "k_acc_A1", "k_acc_Y",
+           "other", "fp64_corrections")
+STAGES = ("g_to_r", "hartree", "occ_occ", "pass_a", "pass_b", "out_and_corrections")
 
 _lib = None
 
@@ -61,6 +67,9 @@ def lib():
         "tc_energy_backward": (I, [P, dp, dp, dp]),
         "tc_sync": (I, [P]),
         "tc_last_timing": (I, [P, dp, dp, I]),
+        "tc_set_batch": (I, [P, I]),
+        "tc_set_profiling": (I, [P, I]),
+        "tc_kernel_stats": (I, [P, dp, dp, dp, I]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -146,10 +155,13 @@ class TCOperator:
     # ---------------------------------------------------------------- work
     @property
     def npw_max(self):
-        return max(self.npw)
+        return max(self.npw) if self.npw else 0
 
     def apply(self) -> List[np.ndarray]:
         nk = len(self.npw)
+        if nk == 0 or self.npw_max == 0 or self.nband == 0:
+            # let the library report the missing set-up (TC_ERR_STATE)
+            self._check(self._L.tc_apply_all(self._h, None), "tc_apply_all")
         out = np.zeros((nk, self.nband, self.npw_max), dtype=np.complex128)
         self._check(self._L.tc_apply_all(self._h, _dp(out.view(np.float64))), "tc_apply_all")
         return [out[k, :, : self.npw[k]] for k in range(nk)]
@@ -176,6 +188,18 @@ class TCOperator:
     def sync(self):
         self._check(self._L.tc_sync(self._h), "tc_sync")
 
+    def set_batch(self, targets_per_batch: int):
+        self._check(self._L.tc_set_batch(self._h, int(targets_per_batch)), "tc_set_batch")
+
+    def set_profiling(self, on: bool):
+        self._check(self._L.tc_set_profiling(self._h, int(bool(on))), "tc_set_profiling")
+
+    def kernel_stats(self, reset: bool = False):
+        n = len(KERNELS)
+        ms, cnt, by = np.zeros(n), np.zeros(n), np.zeros(n)
+        self._check(self._L.tc_kernel_stats(self._h, _dp(ms), _dp(cnt), _dp(by), int(reset)), "tc_kernel_stats")
+        return {f: dict(ms=float(ms[i]), launches=int(cnt[i]), bytes=float(by[i])) for i, f in enumerate(KERNELS)}
+
     def timing(self):
         tot = np.zeros(1)
         st = np.zeros(6)
@@ -184,9 +208,11 @@ class TCOperator:
 
 
 def from_workload(w, precision=TC_PREC_FP64, terms=TERM_ALL, div_correction=True, device=0, A=None, C=None,
-                  coeff=None) -> TCOperator:
+                  coeff=None, stream=None, batch=0) -> TCOperator:
     """Build an operator from a ``tcinputs.Workload`` (TC mode)."""
-    op = TCOperator(device)
+    op = TCOperator(device, stream)
+    if batch:
+        op.set_batch(batch)
     op.set_cell(w.lattice)
     op.set_kmesh(*w.kmesh)
     op.set_grid(*w.grid)

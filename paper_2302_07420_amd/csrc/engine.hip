@@ -88,6 +88,7 @@ struct Problem {
   std::vector<double> occ;                // [nk][nb]
   std::vector<char> loaded;               // per k
   double delta_gb = 0, sigma_aux = 0;
+  int batch = 0;                          // targets per batch (0 = automatic)
 
   int P() const { return nk * nb; }
   long NR() const { return long(N) * N * N; }
@@ -355,26 +356,99 @@ __global__ void k_density64(const cx<double>* psi, const double* w, int P, cx<do
 
 inline unsigned nblk(long n, int b = 256) { return unsigned((n + b - 1) / b); }
 
+// ------------------------------------------------------------------ per-family event timing
+struct Prof {
+  bool on = false;
+  double ms[TC_K_NKERNEL] = {0}, launches[TC_K_NKERNEL] = {0}, bytes[TC_K_NKERNEL] = {0};
+  struct Rec {
+    int fam;
+    hipEvent_t a, b;
+    double bytes;
+  };
+  std::vector<hipEvent_t> pool;
+  size_t used = 0;
+  std::vector<Rec> recs;
+  hipEvent_t get() {
+    if (used == pool.size()) {
+      hipEvent_t e;
+      TC_HIP(hipEventCreate(&e));
+      pool.push_back(e);
+    }
+    return pool[used++];
+  }
+  // call after the stream has been synchronised
+  void collect() {
+    for (const Rec& r : recs) {
+      float t = 0;
+      TC_HIP(hipEventElapsedTime(&t, r.a, r.b));
+      ms[r.fam] += t;
+      launches[r.fam] += 1;
+      bytes[r.fam] += r.bytes;
+    }
+    recs.clear();
+    used = 0;
+  }
+  void reset() {
+    for (int i = 0; i < TC_K_NKERNEL; ++i) ms[i] = launches[i] = bytes[i] = 0;
+  }
+  ~Prof() {
+    for (auto e : pool) (void)hipEventDestroy(e);
+  }
+};
+
+struct ProfScope {
+  Prof* p;
+  hipStream_t s;
+  int fam;
+  double bytes;
+  hipEvent_t a = nullptr;
+  ProfScope(Prof* p_, hipStream_t s_, int f, double b) : p(p_), s(s_), fam(f), bytes(b) {
+    if (p && p->on) {
+      a = p->get();
+      TC_HIP(hipEventRecord(a, s));
+    }
+  }
+  ~ProfScope() noexcept(false) {
+    if (p && p->on) {
+      hipEvent_t b = p->get();
+      TC_HIP(hipEventRecord(b, s));
+      p->recs.push_back({fam, a, b, bytes});
+    }
+  }
+};
+
+template <typename R, int N>
+void fft3d_t(cx<R>* d, long nvol, int dir, hipStream_t s, Prof* pf = nullptr) {
+  if (nvol <= 0) return;
+  constexpr int PB = XY<R, N>::PB;
+  const long np = nvol * N;
+  const double by = 2.0 * double(sizeof(cx<R>)) * nvol * N * N * N;
+  if (dir < 0) {
+    {
+      ProfScope ps(pf, s, TC_K_FFT_XY_FWD, by);
+      hipLaunchKernelGGL((k_fft_xy<R, N, -1>), dim3(nblk(np, PB)), dim3(PB * N), 0, s, d, np);
+    }
+    ProfScope ps(pf, s, TC_K_FFT_Z_FWD, by);
+    hipLaunchKernelGGL((k_fft_z<R, N, -1>), dim3(nblk(nvol * N * N)), dim3(256), 0, s, d, nvol);
+  } else {
+    {
+      ProfScope ps(pf, s, TC_K_FFT_Z_INV, by);
+      hipLaunchKernelGGL((k_fft_z<R, N, 1>), dim3(nblk(nvol * N * N)), dim3(256), 0, s, d, nvol);
+    }
+    ProfScope ps(pf, s, TC_K_FFT_XY_INV, by);
+    hipLaunchKernelGGL((k_fft_xy<R, N, 1>), dim3(nblk(np, PB)), dim3(PB * N), 0, s, d, np);
+  }
+}
+
 // ------------------------------------------------------------------ engine
 struct Engine {
   virtual ~Engine() = default;
   virtual void upload_tables(const Problem& pb) = 0;
   virtual void apply(hipStream_t s, Shared& sh, const Problem& pb, double* stage_ms) = 0;
+  Prof* prof = nullptr;
 };
 
-template <typename R, int N>
-void fft3d_t(cx<R>* d, long nvol, int dir, hipStream_t s) {
-  if (nvol <= 0) return;
-  constexpr int PB = XY<R, N>::PB;
-  const long np = nvol * N;
-  if (dir < 0) {
-    hipLaunchKernelGGL((k_fft_xy<R, N, -1>), dim3(nblk(np, PB)), dim3(PB * N), 0, s, d, np);
-    hipLaunchKernelGGL((k_fft_z<R, N, -1>), dim3(nblk(nvol * N * N)), dim3(256), 0, s, d, nvol);
-  } else {
-    hipLaunchKernelGGL((k_fft_z<R, N, 1>), dim3(nblk(nvol * N * N)), dim3(256), 0, s, d, nvol);
-    hipLaunchKernelGGL((k_fft_xy<R, N, 1>), dim3(nblk(np, PB)), dim3(PB * N), 0, s, d, np);
-  }
-}
+
 
 Masks make_masks(uint64_t m) {
   auto b = [&](uint64_t bit) { return (m & bit) ? 1.0 : 0.0; };
@@ -428,6 +502,7 @@ struct EngineT : Engine {
   DBuf<double> tHu0, tHu1, focc;
   int T = 1;
   int P_alloc = -1;
+  int batch_alloc = -1;
 
   static bool grid_q(const Problem& pb, long r, const double* f, double* Q, double& q2) {
     const int x = int(r % N), y = int((r / N) % N), z = int(r / (N * N));
@@ -511,7 +586,7 @@ struct EngineT : Engine {
 
   void ensure(const Problem& pb, size_t budget_bytes) {
     const int P = pb.P();
-    if (P == P_alloc) return;
+    if (P == P_alloc && pb.batch == batch_alloc) return;
     psi.alloc(size_t(P) * NR);
     D.alloc(size_t(3) * P * NR);
     nJ.alloc(4 * NR);
@@ -521,6 +596,7 @@ struct EngineT : Engine {
     h5.alloc(size_t(P) * NR);
     const size_t per_t = size_t(P) * 13 * NR * sizeof(cx<R>);
     T = int(std::max<size_t>(1, std::min<size_t>(size_t(P), budget_bytes / per_t)));
+    if (pb.batch > 0) T = std::min(pb.batch, P);
     bufA.alloc(size_t(T) * P * 6 * NR);
     bufB.alloc(size_t(T) * P * 7 * NR);
     h4.alloc(size_t(3) * T * NR);
@@ -532,6 +608,7 @@ struct EngineT : Engine {
     prod64.alloc(size_t(2) * P * NR);
     focc.alloc(P);
     P_alloc = P;
+    batch_alloc = pb.batch;
   }
 
   void apply(hipStream_t s, Shared& sh, const Problem& pb, double* stage_ms) override {
@@ -543,59 +620,91 @@ struct EngineT : Engine {
     Recip rc;
     for (int i = 0; i < 9; ++i) rc.b[i] = pb.B[i];
     const Tables tb{tV.p, tU1.p, tU2.p, dfr.p};
-    Events ev(8);
+    // algorithmic bytes: fields each launch must read or write once (working precision)
+    const double fb = double(sizeof(cx<R>)) * NR;
+    const double fd = double(sizeof(cx<double>)) * NR;
+    const double tabB = 3.0 * double(sizeof(R)) * NR * double((2 * pb.n1 - 1) * (2 * pb.n2 - 1) * (2 * pb.n3 - 1));
+    Prof* pf = prof;
+    auto K = [&](int id, double bytes, auto&& launch) {
+      ProfScope ps(pf, s, id, bytes);
+      launch();
+    };
+    Events ev(6);
+    std::vector<hipEvent_t> bev;   // per batch: begin A, end A, end B
     TC_HIP(hipEventRecord(ev.e[0], s));
 
     // ---- 0: G -> r (psi and the three components of D)
     TC_HIP(hipMemsetAsync(psi.p, 0, size_t(P) * NR * sizeof(cx<R>), s));
     TC_HIP(hipMemsetAsync(D.p, 0, size_t(3) * P * NR * sizeof(cx<R>), s));
     const unsigned gsc = nblk(long(P) * pb.npw_max);
-    hipLaunchKernelGGL((k_scatter<R>), dim3(gsc), dim3(256), 0, s, sh.coef.p, sh.boxidx.p, sh.npw.p, sh.kg.p, nb,
-                       pb.npw_max, P, -1, psi.p, NR);
-    for (int c = 0; c < 3; ++c)
+    K(TC_K_SCATTER, 0.0, [&] {
       hipLaunchKernelGGL((k_scatter<R>), dim3(gsc), dim3(256), 0, s, sh.coef.p, sh.boxidx.p, sh.npw.p, sh.kg.p, nb,
-                         pb.npw_max, P, c, D.p + size_t(c) * P * NR, NR);
-    fft3d_t<R, N>(psi.p, P, +1, s);
-    fft3d_t<R, N>(D.p, 3L * P, +1, s);
+                         pb.npw_max, P, -1, psi.p, NR);
+      for (int c = 0; c < 3; ++c)
+        hipLaunchKernelGGL((k_scatter<R>), dim3(gsc), dim3(256), 0, s, sh.coef.p, sh.boxidx.p, sh.npw.p, sh.kg.p, nb,
+                           pb.npw_max, P, c, D.p + size_t(c) * P * NR, NR);
+    });
+    fft3d_t<R, N>(psi.p, P, +1, s, pf);
+    fft3d_t<R, N>(D.p, 3L * P, +1, s, pf);
     TC_HIP(hipEventRecord(ev.e[1], s));
 
     // ---- 1: densities and Hartree-type fields (Algs. 2ah, 3a1, 3b1; 2bh1, 2bh2)
     TC_HIP(hipMemsetAsync(loc.p, 0, 8 * NR * sizeof(cx<R>), s));
-    hipLaunchKernelGGL((k_density<R, N>), dim3(nblk(NR)), dim3(256), 0, s, psi.p, D.p, sh.w.p, P, nJ.p, nJ.p + NR);
+    K(TC_K_OTHER, fb * (4.0 * P + 4.0), [&] {
+      hipLaunchKernelGGL((k_density<R, N>), dim3(nblk(NR)), dim3(256), 0, s, psi.p, D.p, sh.w.p, P, nJ.p, nJ.p + NR);
+    });
     TC_HIP(hipMemcpyAsync(wk.p, nJ.p, 4 * NR * sizeof(cx<R>), hipMemcpyDeviceToDevice, s));
-    fft3d_t<R, N>(wk.p, 4, -1, s);
-    hipLaunchKernelGGL((k_hartree_g<R, N>), dim3(nblk(NR)), dim3(256), 0, s, rc, tHV.p, tHU.p, wk.p, wk.p + NR,
-                       wk.p + 4 * NR);
-    fft3d_t<R, N>(wk.p + 4 * NR, 5, +1, s);
+    fft3d_t<R, N>(wk.p, 4, -1, s, pf);
+    K(TC_K_OTHER, fb * 9.0, [&] {
+      hipLaunchKernelGGL((k_hartree_g<R, N>), dim3(nblk(NR)), dim3(256), 0, s, rc, tHV.p, tHU.p, wk.p, wk.p + NR,
+                         wk.p + 4 * NR);
+    });
+    fft3d_t<R, N>(wk.p + 4 * NR, 5, +1, s, pf);
     TC_HIP(hipMemcpyAsync(loc.p, wk.p + 4 * NR, 5 * NR * sizeof(cx<R>), hipMemcpyDeviceToDevice, s));
-    hipLaunchKernelGGL((k_mul_vec_scalar<R, N>), dim3(nblk(NR)), dim3(256), 0, s, loc.p + NR, nJ.p, wk.p);
-    fft3d_t<R, N>(wk.p, 3, -1, s);
-    hipLaunchKernelGGL((k_gdiv<R, N>), dim3(nblk(NR)), dim3(256), 0, s, rc, tHU.p, wk.p, wk.p + 3 * NR);
-    fft3d_t<R, N>(wk.p + 3 * NR, 1, +1, s);
+    K(TC_K_OTHER, fb * 7.0, [&] {
+      hipLaunchKernelGGL((k_mul_vec_scalar<R, N>), dim3(nblk(NR)), dim3(256), 0, s, loc.p + NR, nJ.p, wk.p);
+    });
+    fft3d_t<R, N>(wk.p, 3, -1, s, pf);
+    K(TC_K_OTHER, fb * 4.0, [&] {
+      hipLaunchKernelGGL((k_gdiv<R, N>), dim3(nblk(NR)), dim3(256), 0, s, rc, tHU.p, wk.p, wk.p + 3 * NR);
+    });
+    fft3d_t<R, N>(wk.p + 3 * NR, 1, +1, s, pf);
     TC_HIP(hipMemcpyAsync(loc.p + 5 * NR, wk.p + 3 * NR, NR * sizeof(cx<R>), hipMemcpyDeviceToDevice, s));
     TC_HIP(hipEventRecord(ev.e[2], s));
 
-    // ---- 2: occupied-occupied pair pass
+    // ---- 2: occupied-occupied pair pass (Algs. 3a2, 3a4 and 3b2/3b5 first loops)
     const bool need_occ = m.m3a2 || m.m3a4 || m.m3b2 || m.m3b5;
     TC_HIP(hipMemsetAsync(H3a4.p, 0, size_t(3) * P * NR * sizeof(cx<R>), s));
     if (need_occ) {
       for (int a0 = 0; a0 < P; a0 += T) {
         const int nt = std::min(T, P - a0);
         const long npair = long(nt) * P;
-        hipLaunchKernelGGL((k_xy_pair<R, N, true>), dim3(nblk(npair * N, PB)), dim3(PB * N), 0, s, psi.p, psi.p,
-                           bufA.p, a0, P, npair * N);
-        hipLaunchKernelGGL((k_zconv<R, N, OP_O>), dim3(nblk(npair * N * N)), dim3(256), 0, s, bufA.p, bufB.p, npair,
-                           a0, mi, rc, tb, 0);
+        K(TC_K_XY_PAIR_OCC, fb * (npair + nt + P), [&] {
+          hipLaunchKernelGGL((k_xy_pair<R, N, true>), dim3(nblk(npair * N, PB)), dim3(PB * N), 0, s, psi.p, psi.p,
+                             bufA.p, a0, P, npair * N);
+        });
+        K(TC_K_ZCONV_OCC, fb * 7.0 * npair + tabB, [&] {
+          hipLaunchKernelGGL((k_zconv<R, N, OP_O>), dim3(nblk(npair * N * N)), dim3(256), 0, s, bufA.p, bufB.p,
+                             npair, a0, mi, rc, tb, 0);
+        });
         const long np = npair * 6 * N;
-        hipLaunchKernelGGL((k_fft_xy<R, N, 1>), dim3(nblk(np, PB)), dim3(PB * N), 0, s, bufB.p, np);
-        hipLaunchKernelGGL((k_acc_O<R, N>), dim3(nblk(long(nt) * NR)), dim3(256), 0, s, bufB.p, psi.p, sh.w.p, P, nt,
-                           a0, h5.p, H3a4.p);
+        K(TC_K_FFT_XY_INV, fb * 12.0 * npair, [&] {
+          hipLaunchKernelGGL((k_fft_xy<R, N, 1>), dim3(nblk(np, PB)), dim3(PB * N), 0, s, bufB.p, np);
+        });
+        K(TC_K_ACC_OCC, fb * (6.0 * npair + P + 3.0 * nt) + 0.5 * fb * nt, [&] {
+          hipLaunchKernelGGL((k_acc_O<R, N>), dim3(nblk(long(nt) * NR)), dim3(256), 0, s, bufB.p, psi.p, sh.w.p, P,
+                             nt, a0, h5.p, H3a4.p);
+        });
       }
-      hipLaunchKernelGGL((k_reduce_occ<R, N>), dim3(nblk(NR)), dim3(256), 0, s, h5.p, H3a4.p, psi.p, sh.w.p, P,
-                         loc.p + 6 * NR, wk.p);
-      fft3d_t<R, N>(wk.p, 3, -1, s);
-      hipLaunchKernelGGL((k_gdiv<R, N>), dim3(nblk(NR)), dim3(256), 0, s, rc, tHU.p, wk.p, wk.p + 3 * NR);
-      fft3d_t<R, N>(wk.p + 3 * NR, 1, +1, s);
+      K(TC_K_OTHER, fb * (5.0 * P + 4.0), [&] {
+        hipLaunchKernelGGL((k_reduce_occ<R, N>), dim3(nblk(NR)), dim3(256), 0, s, h5.p, H3a4.p, psi.p, sh.w.p, P,
+                           loc.p + 6 * NR, wk.p);
+      });
+      fft3d_t<R, N>(wk.p, 3, -1, s, pf);
+      K(TC_K_OTHER, fb * 4.0, [&] {
+        hipLaunchKernelGGL((k_gdiv<R, N>), dim3(nblk(NR)), dim3(256), 0, s, rc, tHU.p, wk.p, wk.p + 3 * NR);
+      });
+      fft3d_t<R, N>(wk.p + 3 * NR, 1, +1, s, pf);
       TC_HIP(hipMemcpyAsync(loc.p + 7 * NR, wk.p + 3 * NR, NR * sizeof(cx<R>), hipMemcpyDeviceToDevice, s));
     }
     TC_HIP(hipEventRecord(ev.e[3], s));
@@ -603,67 +712,111 @@ struct EngineT : Engine {
     // ---- 3/4: target batches (pass A, pass B, local terms, r -> G)
     const bool need_A = m.m2ax || m.m2bx1 || m.m3a3 || m.m3a4 || m.m3b4 || m.m3b6;
     const bool need_B = m.m2bx2 || m.m3b3 || m.m3b4 || m.m3b5;
-    double msA = 0, msB = 0;
     for (int t0 = 0; t0 < P; t0 += T) {
       const int nt = std::min(T, P - t0);
       const long npair = long(nt) * P;
-      Events be(3);
       TC_HIP(hipMemsetAsync(acc.p, 0, size_t(4) * T * NR * sizeof(cx<double>), s));
       TC_HIP(hipMemsetAsync(h4.p, 0, size_t(3) * T * NR * sizeof(cx<R>), s));
-      TC_HIP(hipEventRecord(be.e[0], s));
+      for (int i = 0; i < 3; ++i) {
+        hipEvent_t e;
+        TC_HIP(hipEventCreate(&e));
+        bev.push_back(e);
+      }
+      hipEvent_t* be = &bev[bev.size() - 3];
+      TC_HIP(hipEventRecord(be[0], s));
       if (need_A) {
-        hipLaunchKernelGGL((k_xy_pair<R, N, false>), dim3(nblk(npair * N, PB)), dim3(PB * N), 0, s, psi.p, psi.p,
-                           bufA.p, t0, P, npair * N);
-        hipLaunchKernelGGL((k_zconv<R, N, OP_A1>), dim3(nblk(npair * N * N)), dim3(256), 0, s, bufA.p, bufB.p,
-                           npair, t0, mi, rc, tb, 1);
+        K(TC_K_XY_PAIR_TGT, fb * (npair + nt + P), [&] {
+          hipLaunchKernelGGL((k_xy_pair<R, N, false>), dim3(nblk(npair * N, PB)), dim3(PB * N), 0, s, psi.p, psi.p,
+                             bufA.p, t0, P, npair * N);
+        });
+        K(TC_K_ZCONV_A1, fb * 8.0 * npair + tabB, [&] {
+          hipLaunchKernelGGL((k_zconv<R, N, OP_A1>), dim3(nblk(npair * N * N)), dim3(256), 0, s, bufA.p, bufB.p,
+                             npair, t0, mi, rc, tb, 1);
+        });
         long np = npair * 7 * N;
-        hipLaunchKernelGGL((k_fft_xy<R, N, 1>), dim3(nblk(np, PB)), dim3(PB * N), 0, s, bufB.p, np);
-        hipLaunchKernelGGL((k_acc_A1<R, N>), dim3(nblk(long(nt) * NR)), dim3(256), 0, s, bufB.p, psi.p, D.p, H3a4.p,
-                           sh.w.p, P, nt, m, acc.p, h4.p);
+        K(TC_K_FFT_XY_INV, fb * 14.0 * npair, [&] {
+          hipLaunchKernelGGL((k_fft_xy<R, N, 1>), dim3(nblk(np, PB)), dim3(PB * N), 0, s, bufB.p, np);
+        });
+        K(TC_K_ACC_A1, fb * (4.0 * npair + 7.0 * P + 3.0 * nt) + 6.0 * fd * nt, [&] {
+          hipLaunchKernelGGL((k_acc_A1<R, N>), dim3(nblk(long(nt) * NR)), dim3(256), 0, s, bufB.p, psi.p, D.p,
+                             H3a4.p, sh.w.p, P, nt, m, acc.p, h4.p);
+        });
         if (m.m3b6) {
           np = npair * 6 * N;
-          hipLaunchKernelGGL((k_xy_3b6<R, N>), dim3(nblk(np, PB)), dim3(PB * N), 0, s, bufB.p, nJ.p, bufA.p, np);
-          hipLaunchKernelGGL((k_zconv<R, N, OP_A2>), dim3(nblk(npair * N * N)), dim3(256), 0, s, bufA.p, bufB.p,
-                             npair, t0, mi, rc, tb, 1);
+          K(TC_K_XY_3B6, fb * (12.0 * npair + 1.0), [&] {
+            hipLaunchKernelGGL((k_xy_3b6<R, N>), dim3(nblk(np, PB)), dim3(PB * N), 0, s, bufB.p, nJ.p, bufA.p, np);
+          });
+          K(TC_K_ZCONV_A2, fb * 7.0 * npair + tabB, [&] {
+            hipLaunchKernelGGL((k_zconv<R, N, OP_A2>), dim3(nblk(npair * N * N)), dim3(256), 0, s, bufA.p, bufB.p,
+                               npair, t0, mi, rc, tb, 1);
+          });
           np = npair * N;
-          hipLaunchKernelGGL((k_fft_xy<R, N, 1>), dim3(nblk(np, PB)), dim3(PB * N), 0, s, bufB.p, np);
-          hipLaunchKernelGGL((k_acc_Y<R, N>), dim3(nblk(long(nt) * NR)), dim3(256), 0, s, bufB.p, psi.p, sh.w.p, P,
-                             nt, 1.0, 2, acc.p);
+          K(TC_K_FFT_XY_INV, fb * 2.0 * npair, [&] {
+            hipLaunchKernelGGL((k_fft_xy<R, N, 1>), dim3(nblk(np, PB)), dim3(PB * N), 0, s, bufB.p, np);
+          });
+          K(TC_K_ACC_Y, fb * (npair + P) + 2.0 * fd * nt, [&] {
+            hipLaunchKernelGGL((k_acc_Y<R, N>), dim3(nblk(long(nt) * NR)), dim3(256), 0, s, bufB.p, psi.p, sh.w.p, P,
+                               nt, 1.0, 2, acc.p);
+          });
         }
       }
-      TC_HIP(hipEventRecord(be.e[1], s));
+      TC_HIP(hipEventRecord(be[1], s));
       if (need_B) {
-        hipLaunchKernelGGL((k_passB_Z<R, N>), dim3(nblk(long(nt) * NR)), dim3(256), 0, s, psi.p, D.p, loc.p + NR,
-                           h4.p, t0, nt, P, m, Z.p);
         long np = npair * 3 * N;
-        hipLaunchKernelGGL((k_xy_passB<R, N>), dim3(nblk(np, PB)), dim3(PB * N), 0, s, psi.p, Z.p, H3a4.p, bufA.p,
-                           t0, P, R(m.m3b5), np);
-        hipLaunchKernelGGL((k_zconv<R, N, OP_B>), dim3(nblk(npair * N * N)), dim3(256), 0, s, bufA.p, bufB.p, npair,
-                           t0, mi, rc, tb, 1);
+        K(TC_K_OTHER, fb * 13.0 * nt, [&] {
+          hipLaunchKernelGGL((k_passB_Z<R, N>), dim3(nblk(long(nt) * NR)), dim3(256), 0, s, psi.p, D.p, loc.p + NR,
+                             h4.p, t0, nt, P, m, Z.p);
+        });
+        K(TC_K_XY_PASSB, fb * (3.0 * npair + 4.0 * P + 4.0 * nt), [&] {
+          hipLaunchKernelGGL((k_xy_passB<R, N>), dim3(nblk(np, PB)), dim3(PB * N), 0, s, psi.p, Z.p, H3a4.p, bufA.p,
+                             t0, P, R(m.m3b5), np);
+        });
+        K(TC_K_ZCONV_B, fb * 4.0 * npair + tabB, [&] {
+          hipLaunchKernelGGL((k_zconv<R, N, OP_B>), dim3(nblk(npair * N * N)), dim3(256), 0, s, bufA.p, bufB.p,
+                             npair, t0, mi, rc, tb, 1);
+        });
         np = npair * N;
-        hipLaunchKernelGGL((k_fft_xy<R, N, 1>), dim3(nblk(np, PB)), dim3(PB * N), 0, s, bufB.p, np);
-        hipLaunchKernelGGL((k_acc_Y<R, N>), dim3(nblk(long(nt) * NR)), dim3(256), 0, s, bufB.p, psi.p, sh.w.p, P, nt,
-                           1.0, 3, acc.p);
+        K(TC_K_FFT_XY_INV, fb * 2.0 * npair, [&] {
+          hipLaunchKernelGGL((k_fft_xy<R, N, 1>), dim3(nblk(np, PB)), dim3(PB * N), 0, s, bufB.p, np);
+        });
+        K(TC_K_ACC_Y, fb * (npair + P) + 2.0 * fd * nt, [&] {
+          hipLaunchKernelGGL((k_acc_Y<R, N>), dim3(nblk(long(nt) * NR)), dim3(256), 0, s, bufB.p, psi.p, sh.w.p, P,
+                             nt, 1.0, 3, acc.p);
+        });
       }
-      TC_HIP(hipEventRecord(be.e[2], s));
-      hipLaunchKernelGGL((k_local<R, N>), dim3(nblk(long(nt) * NR)), dim3(256), 0, s, psi.p, D.p, loc.p, h4.p, t0, nt,
-                         P, m, acc.p, g.p);
-      hipLaunchKernelGGL((k_epart<R, N>), dim3(4 * nt), dim3(256), 0, s, psi.p, acc.p, t0, nt, sh.epart.p);
-      fft3d_t<R, N>(g.p, nt, -1, s);
-      hipLaunchKernelGGL((k_gather<R>), dim3(nblk(long(nt) * pb.npw_max)), dim3(256), 0, s, g.p, sh.boxidx.p,
-                         sh.npw.p, nb, pb.npw_max, t0, nt, 1.0 / double(NR), sh.out.p, NR);
-      TC_HIP(hipEventSynchronize(be.e[2]));
-      msA += be.ms(0, 1);
-      msB += be.ms(1, 2);
+      TC_HIP(hipEventRecord(be[2], s));
+      K(TC_K_OTHER, fb * 16.0 * nt + 8.0 * fd * nt, [&] {
+        hipLaunchKernelGGL((k_local<R, N>), dim3(nblk(long(nt) * NR)), dim3(256), 0, s, psi.p, D.p, loc.p, h4.p, t0,
+                           nt, P, m, acc.p, g.p);
+        hipLaunchKernelGGL((k_epart<R, N>), dim3(4 * nt), dim3(256), 0, s, psi.p, acc.p, t0, nt, sh.epart.p);
+      });
+      fft3d_t<R, N>(g.p, nt, -1, s, pf);
+      K(TC_K_OTHER, 0.0, [&] {
+        hipLaunchKernelGGL((k_gather<R>), dim3(nblk(long(nt) * pb.npw_max)), dim3(256), 0, s, g.p, sh.boxidx.p,
+                           sh.npw.p, nb, pb.npw_max, t0, nt, 1.0 / double(NR), sh.out.p, NR);
+      });
     }
     TC_HIP(hipEventRecord(ev.e[4], s));
 
     // ---- 5: kinetic energy and FP64 corrections
-    hipLaunchKernelGGL(k_kinetic, dim3(P), dim3(256), 0, s, sh.coef.p, sh.kg.p, sh.npw.p, nb, pb.npw_max, sh.tkin.p);
-    TC_HIP(hipMemsetAsync(sh.ecorr.p, 0, size_t(2) * P * sizeof(double), s));
-    if (pb.div && (pb.mask & TC_T_CORR) && (m.m2ax || m.m3a2 || m.m3b6)) corrections(s, sh, pb, m);
+    K(TC_K_CORR, 0.0, [&] {
+      hipLaunchKernelGGL(k_kinetic, dim3(P), dim3(256), 0, s, sh.coef.p, sh.kg.p, sh.npw.p, nb, pb.npw_max,
+                         sh.tkin.p);
+      TC_HIP(hipMemsetAsync(sh.ecorr.p, 0, size_t(2) * P * sizeof(double), s));
+      if (pb.div && (pb.mask & TC_T_CORR) && (m.m2ax || m.m3a2 || m.m3b6)) corrections(s, sh, pb, m);
+    });
     TC_HIP(hipEventRecord(ev.e[5], s));
     TC_HIP(hipEventSynchronize(ev.e[5]));
+    if (pf && pf->on) pf->collect();
+    double msA = 0, msB = 0;
+    for (size_t i = 0; i + 2 < bev.size(); i += 3) {
+      float a = 0, b = 0;
+      TC_HIP(hipEventElapsedTime(&a, bev[i], bev[i + 1]));
+      TC_HIP(hipEventElapsedTime(&b, bev[i + 1], bev[i + 2]));
+      msA += a;
+      msB += b;
+    }
+    for (auto e : bev) (void)hipEventDestroy(e);
     stage_ms[0] = ev.ms(0, 1);
     stage_ms[1] = ev.ms(1, 2);
     stage_ms[2] = ev.ms(2, 3);
@@ -786,6 +939,7 @@ struct tc_ctx {
   double e_total = 0, e_parts[TC_E_NPARTS] = {0, 0, 0, 0};
   double stage_ms[6] = {0, 0, 0, 0, 0, 0};
   double total_ms = 0;
+  Prof prof;
 };
 
 namespace {
@@ -879,6 +1033,7 @@ int do_apply(tc_ctx* c, void* out_dev, double* out_host) {
   sh.ecorr.alloc(size_t(2) * P);
   sh.S.alloc(size_t(2) * pb.nk * pb.nb * pb.nb);
   sh.O.alloc(size_t(2) * pb.nk * pb.nb * pb.nb);
+  c->eng->prof = &c->prof;
   c->eng->apply(c->stream, sh, pb, c->stage_ms);
   c->total_ms = 0;
   for (double v : c->stage_ms) c->total_ms += v;
@@ -1167,6 +1322,34 @@ int tc_energy_backward(tc_ctx* c, double* grad, double dA[2], double dC[2]) {
 int tc_sync(tc_ctx* c) {
   return guard(c, [&]() -> int {
     TC_HIP(hipStreamSynchronize(c->stream));
+    return TC_OK;
+  });
+}
+
+int tc_set_batch(tc_ctx* c, int targets_per_batch) {
+  return guard(c, [&]() -> int {
+    if (targets_per_batch < 0) return fail(c, TC_ERR_ARG, "batch must be >= 0");
+    c->pb.batch = targets_per_batch;
+    c->have_result = false;
+    return TC_OK;
+  });
+}
+
+int tc_set_profiling(tc_ctx* c, int on) {
+  return guard(c, [&]() -> int {
+    c->prof.on = on != 0;
+    return TC_OK;
+  });
+}
+
+int tc_kernel_stats(tc_ctx* c, double* ms, double* launches, double* bytes, int reset) {
+  return guard(c, [&]() -> int {
+    for (int i = 0; i < TC_K_NKERNEL; ++i) {
+      if (ms) ms[i] = c->prof.ms[i];
+      if (launches) launches[i] = c->prof.launches[i];
+      if (bytes) bytes[i] = c->prof.bytes[i];
+    }
+    if (reset) c->prof.reset();
     return TC_OK;
   });
 }

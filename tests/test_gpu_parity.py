@@ -1,0 +1,129 @@
+"""Parity of the HIP path with the FP64 oracle, element by element, through the C ABI."""
+import numpy as np
+import pytest
+
+import tcinputs as T
+from oracle.fftroute import ALL_TERMS, MULT, Problem
+from oracle.heg import heg_energy
+
+pytestmark = pytest.mark.gpu
+
+tc = pytest.importorskip("paper_2302_07420_amd")
+
+FP64_TOL = 1e-10      # relative, FP64 GPU vs FP64 oracle
+FP32_TOL = 2e-6       # relative per result (max norm), FP32 GPU vs FP64 oracle
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def oracle(w, terms=ALL_TERMS, div=True):
+    pr = Problem(w, div_correction=div)
+    per = {t: [c.numpy() for c in pr.to_coeff(MULT.get(t, 1) * pr.term(t, 0))] for t in terms}
+    tot = [sum(per[t][k] for t in terms) for k in range(w.nk)]
+    return per, tot, float(pr.energy(terms=terms))
+
+
+def relerr(a, b):
+    scale = max(np.abs(x).max() for x in b)
+    return max(np.abs(x - y).max() for x, y in zip(a, b)) / scale
+
+
+CASES = {
+    "fcc_k211_g8_partial": lambda: T.tiny_fcc(kmesh=(2, 1, 1), grid=8, ecut=2.0, nb=2, a=6.0, occ=[1.0, 0.7]),
+    "fcc_k222_g12_empty_band": lambda: T.tiny_fcc(kmesh=(2, 2, 2), grid=12, ecut=2.0, nb=3, a=6.0,
+                                                   occ=[1.0, 0.9, 0.0]),
+    "fcc_k121_g16_nb1": lambda: T.tiny_fcc(kmesh=(1, 2, 1), grid=16, ecut=3.0, nb=1, a=7.0),
+}
+
+
+@pytest.fixture(scope="module", params=list(CASES))
+def case(request):
+    w = CASES[request.param]()
+    return request.param, w, oracle(w)
+
+
+def test_every_term_fp64(case):
+    name, w, (per, tot, E) = case
+    for t in ALL_TERMS:
+        _say(f"[gpu] {name} fp64 term {t}")
+        op = tc.from_workload(w, precision=tc.TC_PREC_FP64, terms=tc.TERM_BITS[t] | tc.TERM_BITS["corr"])
+        hc = op.apply()
+        op.close()
+        scale = max(max(np.abs(x).max() for x in tot), 1e-300)
+        err = max(np.abs(h - r).max() for h, r in zip(hc, per[t])) / scale
+        assert err < FP64_TOL, (t, err)
+
+
+@pytest.mark.parametrize("batch", [0, 1, 3])
+def test_total_and_energy_fp64_with_batching(case, batch):
+    name, w, (per, tot, E) = case
+    _say(f"[gpu] {name} fp64 all terms batch={batch}")
+    op = tc.from_workload(w, precision=tc.TC_PREC_FP64, batch=batch)
+    hc = op.apply()
+    Eg, parts = op.energy()
+    op.close()
+    assert relerr(hc, tot) < FP64_TOL
+    assert abs(Eg - E) < FP64_TOL * abs(E)
+
+
+def test_total_and_energy_fp32(case):
+    name, w, (per, tot, E) = case
+    _say(f"[gpu] {name} fp32 all terms")
+    op = tc.from_workload(w, precision=tc.TC_PREC_FP32, batch=2)
+    hc = op.apply()
+    Eg, _ = op.energy()
+    op.close()
+    assert relerr(hc, tot) < FP32_TOL
+    assert abs(Eg - E) < 1e-6 * abs(E)
+
+
+def test_electron_gas_closed_form_fp64():
+    w = T.config(1)
+    _say("[gpu] heg14 gamma 16^3 fp64 vs closed forms")
+    op = tc.from_workload(w, precision=tc.TC_PREC_FP64)
+    Eg, parts = op.energy()
+    op.close()
+    Eh, _ = heg_energy(w)
+    assert abs(Eg - Eh) < 1e-10 * abs(Eh)
+
+
+def test_hartree_fock_limit_fp64():
+    w = T.config(1).replace(A=(0.0, 0.0))
+    _say("[gpu] heg14 A=0 (Hartree-Fock) fp64")
+    op = tc.from_workload(w, precision=tc.TC_PREC_FP64)
+    Eg, parts = op.energy()
+    op.close()
+    # exchange = total - kinetic; closed form with the GB correction
+    assert parts["two_body"] == pytest.approx(-1.8003924344714473, rel=1e-10)
+    assert parts["three_body"] == pytest.approx(0.0, abs=1e-14)
+
+
+def test_no_correction_option_fp64():
+    w = CASES["fcc_k211_g8_partial"]()
+    _, tot, E = oracle(w, div=False)
+    _say("[gpu] fcc_k211 fp64 without divergence corrections")
+    op = tc.from_workload(w, precision=tc.TC_PREC_FP64, div_correction=False)
+    hc = op.apply()
+    Eg, _ = op.energy()
+    op.close()
+    assert relerr(hc, tot) < FP64_TOL
+    assert abs(Eg - E) < FP64_TOL * abs(E)
+
+
+def test_error_paths():
+    _say("[gpu] error paths")
+    op = tc.TCOperator(0)
+    with pytest.raises(tc.TCError, match="status -5"):
+        op.set_grid(20, 20, 20)
+    with pytest.raises(tc.TCError, match="status -2"):
+        op.apply()
+    op.set_cell(T.fcc_lattice(6.0))
+    op.set_kmesh(1, 1, 1)
+    op.set_grid(8, 8, 8)
+    with pytest.raises(tc.TCError, match="status -3"):
+        op.set_basis(0, np.array([[4, 0, 0]]))
+    with pytest.raises(tc.TCError, match="status -1"):
+        op.set_jastrow([1.0, 1.0], [0.0, 1.0])
+    op.close()
