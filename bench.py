@@ -119,6 +119,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 GPU path")
     ap.add_argument("--config", type=int, default=2, help="workload: 1, 2 (default), 3 or 4")
+    ap.add_argument("--copy-calib-mib", type=int, default=0,
+                    help="run one plain device copy of this many MiB first (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: this build has no multi-GPU path (asked for --gpus {args.gpus})",
@@ -135,6 +137,15 @@ def main():
     torch.cuda.set_stream(side)
     stream = side.cuda_stream
     out = torch.empty((w.nk, w.nband, max(m.shape[0] for m in w.miller)), dtype=torch.complex128, device="cuda")
+    if args.copy_calib_mib > 0:
+        n = args.copy_calib_mib << 20
+        src = torch.ones(n, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy calibration: {n} bytes read + {n} bytes written")
+        del src, dst
 
     op32, keep32 = make_op(w, tc.TC_PREC_FP32, stream)
     ms32, wall32, e32, stats = time_steps(op32, out, args.steps, args.warmup, profile=True)

@@ -493,7 +493,12 @@ struct EngineT : Engine {
   DBuf<cx<R>> bufB;    // [T*P][7][NR]
   DBuf<cx<R>> h4, Z;   // [T][3][NR]
   DBuf<cx<R>> g;       // [T][NR]
-  DBuf<cx<double>> acc;  // [4][T][NR]
+  DBuf<cx<double>> acc;     // [4][T][NR]  FP64 accumulation of the operator output, per energy slot
+  DBuf<cx<R>> gpart;        // [S][T][3][NR]  partner-chunk partials
+  DBuf<cx<R>> h4part;       // [S][T][3][NR]
+  DBuf<R> h5part;           // [S][T][NR]
+  DBuf<cx<R>> H3part;       // [S][T][3][NR]
+  int S = 1;
   // kernel tables (scaled by 1/(Omega N^3))
   DBuf<R> tV, tU1, tU2, tHV, tHU;
   DBuf<double> dfr;
@@ -603,6 +608,13 @@ struct EngineT : Engine {
     Z.alloc(size_t(3) * T * NR);
     g.alloc(size_t(T) * NR);
     acc.alloc(size_t(4) * T * NR);
+    // partner chunks: enough work-groups (targets x z-planes x chunks) to fill the chip,
+    // at most 64 partners per chunk (working-precision partial sums)
+    S = int(std::min<long>(P, std::max<long>({1L, (2048 + long(T) * N - 1) / (long(T) * N), (P + 63L) / 64})));
+    gpart.alloc(size_t(S) * 3 * T * NR);
+    h4part.alloc(size_t(S) * 3 * T * NR);
+    h5part.alloc(size_t(S) * T * NR);
+    H3part.alloc(size_t(S) * 3 * T * NR);
     psi64.alloc(size_t(P) * NR);
     v64.alloc(4 * NR);
     prod64.alloc(size_t(2) * P * NR);
@@ -674,11 +686,13 @@ struct EngineT : Engine {
 
     // ---- 2: occupied-occupied pair pass (Algs. 3a2, 3a4 and 3b2/3b5 first loops)
     const bool need_occ = m.m3a2 || m.m3a4 || m.m3b2 || m.m3b5;
+    const int chunk = (P + S - 1) / S;
     TC_HIP(hipMemsetAsync(H3a4.p, 0, size_t(3) * P * NR * sizeof(cx<R>), s));
     if (need_occ) {
       for (int a0 = 0; a0 < P; a0 += T) {
         const int nt = std::min(T, P - a0);
         const long npair = long(nt) * P;
+        const FusedArgs fa{P, nt, a0, S, chunk};
         K(TC_K_XY_PAIR_OCC, fb * (npair + nt + P), [&] {
           hipLaunchKernelGGL((k_xy_pair<R, N, true>), dim3(nblk(npair * N, PB)), dim3(PB * N), 0, s, psi.p, psi.p,
                              bufA.p, a0, P, npair * N);
@@ -687,13 +701,13 @@ struct EngineT : Engine {
           hipLaunchKernelGGL((k_zconv<R, N, OP_O>), dim3(nblk(npair * N * N)), dim3(256), 0, s, bufA.p, bufB.p,
                              npair, a0, mi, rc, tb, 0);
         });
-        const long np = npair * 6 * N;
-        K(TC_K_FFT_XY_INV, fb * 12.0 * npair, [&] {
-          hipLaunchKernelGGL((k_fft_xy<R, N, 1>), dim3(nblk(np, PB)), dim3(PB * N), 0, s, bufB.p, np);
+        K(TC_K_ACC_OCC, fb * (6.0 * npair + P) + 4.0 * fb * nt * S, [&] {
+          hipLaunchKernelGGL((k_fused_O<R, N>), dim3(unsigned(nt) * N * S), dim3(Fz<R, N>::NTH), 0, s, bufB.p, psi.p,
+                             sh.w.p, fa, h5part.p, H3part.p);
         });
-        K(TC_K_ACC_OCC, fb * (6.0 * npair + P + 3.0 * nt) + 0.5 * fb * nt, [&] {
-          hipLaunchKernelGGL((k_acc_O<R, N>), dim3(nblk(long(nt) * NR)), dim3(256), 0, s, bufB.p, psi.p, sh.w.p, P,
-                             nt, a0, h5.p, H3a4.p);
+        K(TC_K_OTHER, 4.0 * fb * nt * (S + 1), [&] {
+          hipLaunchKernelGGL((k_sum_parts<R, N>), dim3(nblk(long(nt) * NR)), dim3(256), 0, s, 0, S, nt, a0, 0,
+                             h5part.p, H3part.p, nullptr, nullptr, h5.p, H3a4.p, nullptr, nullptr);
         });
       }
       K(TC_K_OTHER, fb * (5.0 * P + 4.0), [&] {
@@ -724,6 +738,7 @@ struct EngineT : Engine {
       }
       hipEvent_t* be = &bev[bev.size() - 3];
       TC_HIP(hipEventRecord(be[0], s));
+      const double part = fb * nt * S;   // one working-precision field per (chunk, target)
       if (need_A) {
         K(TC_K_XY_PAIR_TGT, fb * (npair + nt + P), [&] {
           hipLaunchKernelGGL((k_xy_pair<R, N, false>), dim3(nblk(npair * N, PB)), dim3(PB * N), 0, s, psi.p, psi.p,
@@ -733,36 +748,33 @@ struct EngineT : Engine {
           hipLaunchKernelGGL((k_zconv<R, N, OP_A1>), dim3(nblk(npair * N * N)), dim3(256), 0, s, bufA.p, bufB.p,
                              npair, t0, mi, rc, tb, 1);
         });
-        long np = npair * 7 * N;
-        K(TC_K_FFT_XY_INV, fb * 14.0 * npair, [&] {
-          hipLaunchKernelGGL((k_fft_xy<R, N, 1>), dim3(nblk(np, PB)), dim3(PB * N), 0, s, bufB.p, np);
+        const FusedArgs fa{P, nt, t0, S, chunk};
+        K(TC_K_ACC_A1, fb * ((m.m3b6 ? 13.0 : 7.0) * npair + 8.0 * P + nt) + 6.0 * part, [&] {
+          hipLaunchKernelGGL((k_fused_A<R, N>), dim3(unsigned(nt) * N * S), dim3(Fz<R, N>::NTH), 0, s, bufB.p, psi.p,
+                             D.p, H3a4.p, nJ.p, sh.w.p, fa, m, int(m.m3b6 != 0), bufA.p, gpart.p, h4part.p);
         });
-        K(TC_K_ACC_A1, fb * (4.0 * npair + 7.0 * P + 3.0 * nt) + 6.0 * fd * nt, [&] {
-          hipLaunchKernelGGL((k_acc_A1<R, N>), dim3(nblk(long(nt) * NR)), dim3(256), 0, s, bufB.p, psi.p, D.p,
-                             H3a4.p, sh.w.p, P, nt, m, acc.p, h4.p);
+        K(TC_K_OTHER, 6.0 * part + 6.0 * fd * nt + 3.0 * fb * nt, [&] {
+          hipLaunchKernelGGL((k_sum_parts<R, N>), dim3(nblk(long(nt) * NR)), dim3(256), 0, s, 1, S, nt, t0, 0, nullptr,
+                             nullptr, gpart.p, h4part.p, nullptr, nullptr, acc.p, h4.p);
         });
         if (m.m3b6) {
-          np = npair * 6 * N;
-          K(TC_K_XY_3B6, fb * (12.0 * npair + 1.0), [&] {
-            hipLaunchKernelGGL((k_xy_3b6<R, N>), dim3(nblk(np, PB)), dim3(PB * N), 0, s, bufB.p, nJ.p, bufA.p, np);
-          });
           K(TC_K_ZCONV_A2, fb * 7.0 * npair + tabB, [&] {
             hipLaunchKernelGGL((k_zconv<R, N, OP_A2>), dim3(nblk(npair * N * N)), dim3(256), 0, s, bufA.p, bufB.p,
                                npair, t0, mi, rc, tb, 1);
           });
-          np = npair * N;
-          K(TC_K_FFT_XY_INV, fb * 2.0 * npair, [&] {
-            hipLaunchKernelGGL((k_fft_xy<R, N, 1>), dim3(nblk(np, PB)), dim3(PB * N), 0, s, bufB.p, np);
+          K(TC_K_ACC_Y, fb * (npair + P) + part, [&] {
+            hipLaunchKernelGGL((k_fused_Y<R, N>), dim3(unsigned(nt) * N * S), dim3(Fz<R, N>::NTH), 0, s, bufB.p,
+                               psi.p, sh.w.p, fa, 1.0, gpart.p);
           });
-          K(TC_K_ACC_Y, fb * (npair + P) + 2.0 * fd * nt, [&] {
-            hipLaunchKernelGGL((k_acc_Y<R, N>), dim3(nblk(long(nt) * NR)), dim3(256), 0, s, bufB.p, psi.p, sh.w.p, P,
-                               nt, 1.0, 2, acc.p);
+          K(TC_K_OTHER, part + 2.0 * fd * nt, [&] {
+            hipLaunchKernelGGL((k_sum_parts<R, N>), dim3(nblk(long(nt) * NR)), dim3(256), 0, s, 2, S, nt, t0, 2,
+                               nullptr, nullptr, gpart.p, nullptr, nullptr, nullptr, acc.p, nullptr);
           });
         }
       }
       TC_HIP(hipEventRecord(be[1], s));
       if (need_B) {
-        long np = npair * 3 * N;
+        const long np = npair * 3 * N;
         K(TC_K_OTHER, fb * 13.0 * nt, [&] {
           hipLaunchKernelGGL((k_passB_Z<R, N>), dim3(nblk(long(nt) * NR)), dim3(256), 0, s, psi.p, D.p, loc.p + NR,
                              h4.p, t0, nt, P, m, Z.p);
@@ -775,13 +787,14 @@ struct EngineT : Engine {
           hipLaunchKernelGGL((k_zconv<R, N, OP_B>), dim3(nblk(npair * N * N)), dim3(256), 0, s, bufA.p, bufB.p,
                              npair, t0, mi, rc, tb, 1);
         });
-        np = npair * N;
-        K(TC_K_FFT_XY_INV, fb * 2.0 * npair, [&] {
-          hipLaunchKernelGGL((k_fft_xy<R, N, 1>), dim3(nblk(np, PB)), dim3(PB * N), 0, s, bufB.p, np);
+        const FusedArgs fy{P, nt, t0, S, chunk};
+        K(TC_K_ACC_Y, fb * (npair + P) + part, [&] {
+          hipLaunchKernelGGL((k_fused_Y<R, N>), dim3(unsigned(nt) * N * S), dim3(Fz<R, N>::NTH), 0, s, bufB.p, psi.p,
+                             sh.w.p, fy, 1.0, gpart.p);
         });
-        K(TC_K_ACC_Y, fb * (npair + P) + 2.0 * fd * nt, [&] {
-          hipLaunchKernelGGL((k_acc_Y<R, N>), dim3(nblk(long(nt) * NR)), dim3(256), 0, s, bufB.p, psi.p, sh.w.p, P,
-                             nt, 1.0, 3, acc.p);
+        K(TC_K_OTHER, part + 2.0 * fd * nt, [&] {
+          hipLaunchKernelGGL((k_sum_parts<R, N>), dim3(nblk(long(nt) * NR)), dim3(256), 0, s, 2, S, nt, t0, 3, nullptr,
+                             nullptr, gpart.p, nullptr, nullptr, nullptr, acc.p, nullptr);
         });
       }
       TC_HIP(hipEventRecord(be[2], s));

@@ -259,31 +259,6 @@ __global__ void __launch_bounds__(256) k_xy_pair(const cx<R>* X, const cx<R>* Y,
   xy_block<R, N, -1>(io, nplanes);
 }
 
-// Sources of the 3b6 chain: S_{s,c} = X^{U,s}_c * n for s in {par, anti}; buf7 holds
-// [XV, XU_par x3, XU_anti x3] in real space per pair; output [pair][6][N^3], forward xy.
-template <typename R, int N>
-struct IO3b6 {
-  const cx<R>* buf7;
-  const cx<R>* n;
-  cx<R>* out;
-  __device__ cx<R> load(long pl, int y, int x) const {
-    constexpr long NR = long(N) * N * N;
-    const long f = pl / N;              // pair*6 + comp
-    const int z = int(pl - f * N);
-    const long pair = f / 6;
-    const int comp = int(f - pair * 6);
-    const long o = long(z) * N * N + y * N + x;
-    return buf7[(pair * 7 + 1 + comp) * NR + o] * n[o];
-  }
-  __device__ void store(long pl, int y, int x, cx<R> v) const { out[pl * N * N + y * N + x] = v; }
-};
-
-template <typename R, int N>
-__global__ void __launch_bounds__(256) k_xy_3b6(const cx<R>* buf7, const cx<R>* n, cx<R>* out, long nplanes) {
-  IO3b6<R, N> io{buf7, n, out};
-  xy_block<R, N, -1>(io, nplanes);
-}
-
 // Pass-B sources: Y_c = conj(psi_q) Z_tc + m3b5 * H3b_qc * psi_j, H3b = conj(H3a4) (TC mode);
 // Z holds D_j - h1 psi_j + h4_j (masked) per target.
 template <typename R, int N>
@@ -427,110 +402,388 @@ __global__ void __launch_bounds__(256) k_zconv(const cx<R>* in, cx<R>* out, long
   }
 }
 
-// ---------------------------------------------------------------- partner sums (FP64)
+// ---------------------------------------------------------------- masks
 struct Masks {
   double m2ah, m2bh1, m2bh2, m2ax, m2bx1, m2bx2, m3a1, m3a2, m3a3, m3a4, m3b1, m3b2, m3b3, m3b4, m3b5, m3b6;
 };
 
-// Pass A, first stage.  buf7 (real space) per pair: [XV, XU_par(3), XU_anti(3)].
-// acc layout [4][T][N^3] complex128: 0 = 2ah/2ax, 1 = 2bh1/2bx1, 2 = three-body, 3 = pass B/2bh2.
+// ---------------------------------------------------------------- fused inverse-xy + partner sums
+// A work-group owns one target t, one z-plane and one chunk of partners.  For
+// every partner it loads the z-stage outputs of the pair (xy still in G space),
+// finishes the 3D inverse transform with an in-LDS xy transform and accumulates
+// the pair's contributions for the N^2 points of its plane in registers.
+// Thread layout: RB rows x N columns; thread (y0, x) owns the points (y0 + RB i, x)
+// and, in the transform passes, one line.  Partner sums run in the working
+// precision inside a chunk (<= 64 partners) and in FP64 across chunks.
 template <typename R, int N>
-__global__ void k_acc_A1(const cx<R>* buf7, const cx<R>* psi, const cx<R>* D, const cx<R>* H3a4, const double* w,
-                         int P, int T, Masks mk_, cx<double>* acc, cx<R>* h4) {
-  constexpr long NR = long(N) * N * N;
-  const long id = long(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (id >= long(T) * NR) return;
-  const int t = int(id / NR);
-  const long r = id - long(t) * NR;
-  double a0r = 0, a0i = 0, a1r = 0, a1i = 0, a2r = 0, a2i = 0;
-  double hr[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
-  for (int q = 0; q < P; ++q) {
-    const cx<R>* b = buf7 + (long(t) * P + q) * 7 * NR + r;
-    const double wq = w[q];
-    const cx<R> pq = psi[long(q) * NR + r];
-    const cx<R> XV = b[0];
-    const cx<R> v = XV * pq;
-    a0r -= wq * double(v.x);
-    a0i -= wq * double(v.y);
-    cx<R> sd = mk<R>(R(0), R(0)), sh = mk<R>(R(0), R(0));
+struct Fz {
+  static constexpr int RB = (N % 8 == 0) ? 8 : 4;
+  static constexpr int NTH = RB * N;                                    // threads per work-group
+  static constexpr int KP = N / RB;                                     // owned points per thread
+  static constexpr int LD = N + 1;
+  static constexpr int PLANE = N * LD;                                  // LDS elements per plane
+  static constexpr int kBudget = 65536;
+  static constexpr int kFit = kBudget / int(PLANE * sizeof(cx<R>));
+  static constexpr int GRP0 = kFit < 1 ? 1 : kFit;
+  static constexpr int GRP = GRP0 < RB ? GRP0 : RB;                    // planes in LDS at once (<= RB lines/thread)
+};
+
+// in-place 2D transform of np <= RB planes in LDS ([np][N][N+1]); ends with a barrier
+template <typename R, int N, int DIR>
+__device__ __forceinline__ void planes_fft(cx<R>* sm, int np, int tid) {
+  constexpr int LD = N + 1;
+  const int p = tid / N, l = tid - (tid / N) * N;
+  const bool act = p < np;
+  if (act) {
+    cx<R> v[N];
+    cx<R>* row = sm + (p * N + l) * LD;
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      const cx<R> XU = b[(1 + c) * NR];
-      sd = sd + XU * D[(long(c) * P + q) * NR + r];
-      sh = sh + XU * H3a4[(long(q) * 3 + c) * NR + r];
-      const cx<R> hv = XU * pq;
-      hr[c] += wq * double(hv.x);
-      hi[c] += wq * double(hv.y);
-    }
-    a1r -= wq * double(sd.x);
-    a1i -= wq * double(sd.y);
-    a2r -= wq * double(sh.x);
-    a2i -= wq * double(sh.y);
+    for (int x = 0; x < N; ++x) v[x] = row[x];
+    fft_line<R, N, DIR>(v);
+#pragma unroll
+    for (int x = 0; x < N; ++x) row[x] = v[x];
   }
-  cx<double>* A0 = acc + long(t) * NR + r;
-  const long TS = long(T) * NR;
-  A0[0].x += mk_.m2ax * a0r;
-  A0[0].y += mk_.m2ax * a0i;
-  A0[TS].x += mk_.m2bx1 * a1r;
-  A0[TS].y += mk_.m2bx1 * a1i;
-  A0[2 * TS].x += mk_.m3a4 * a2r;
-  A0[2 * TS].y += mk_.m3a4 * a2i;
+  __syncthreads();
+  if (act) {
+    cx<R> v[N];
+    cx<R>* col = sm + p * N * LD + l;
 #pragma unroll
-  for (int c = 0; c < 3; ++c) h4[(long(t) * 3 + c) * NR + r] = mk<R>(R(hr[c]), R(hi[c]));
+    for (int y = 0; y < N; ++y) v[y] = col[y * LD];
+    fft_line<R, N, DIR>(v);
+#pragma unroll
+    for (int y = 0; y < N; ++y) col[y * LD] = v[y];
+  }
+  __syncthreads();
 }
 
-// acc[slot][t] += sign * sum_q w_q Y_tq psi_q   (Y: one field per pair, real space)
-template <typename R, int N>
-__global__ void k_acc_Y(const cx<R>* Y, const cx<R>* psi, const double* w, int P, int T, double coef, int slot,
-                        cx<double>* acc) {
-  constexpr long NR = long(N) * N * N;
-  const long id = long(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (id >= long(T) * NR) return;
-  const int t = int(id / NR);
-  const long r = id - long(t) * NR;
-  double ar = 0, ai = 0;
-  for (int q = 0; q < P; ++q) {
-    const cx<R> v = Y[(long(t) * P + q) * NR + r] * psi[long(q) * NR + r];
-    ar += w[q] * double(v.x);
-    ai += w[q] * double(v.y);
-  }
-  cx<double>* A = acc + long(slot) * T * NR + long(t) * NR + r;
-  A->x += coef * ar;
-  A->y += coef * ai;
+struct FusedArgs {
+  int P, T, t0, S, chunk;     // orbitals, targets in batch, first target, partner chunks, partners per chunk
+};
+
+template <typename R>
+__device__ __forceinline__ void cfma(cx<R>& acc, R a, cx<R> u, cx<R> v) {   // acc += a u v
+  const cx<R> p = u * v;
+  acc.x += a * p.x;
+  acc.y += a * p.y;
 }
 
-// Occupied-occupied pass: buf6 per pair (a = t0+t, b = q): [V_par(3), V_anti(3)], real space.
-// h5[a] = sum_b w_b (|V_par|^2 + |V_anti|^2)   (TC mode: V_ba = conj(V_ab), Alg. 3a2)
-// H3a4[a]_c = sum_b w_b conj(V_par,c) psi_b    (Alg. 3a4 h3; Alg. 3b2 h3 = conj of it)
+// Pass A: buf7 per pair [XV, XU_par(3), XU_anti(3)] (xy in G space).  Slots:
+//   0: -m2ax w XV psi_q          (2ax)
+//   1: -m2bx1 w XU . D_q         (2bx1)
+//   2: -m3a4 w H3a4_q . XU       (2 x 3a4)
+//   h4 += w XU psi_q             (h4 of Alg. 3a3)
+// and, if do3b6, writes the 3b6 sources S_{s,c} = X^{U,s}_c n, forward xy transformed.
 template <typename R, int N>
-__global__ void k_acc_O(const cx<R>* buf6, const cx<R>* psi, const double* w, int P, int T, int t0, R* h5,
-                        cx<R>* H3a4) {
+__global__ void __launch_bounds__((Fz<R, N>::NTH)) k_fused_A(const cx<R>* buf7, const cx<R>* psi, const cx<R>* D,
+                                                           const cx<R>* H3a4, const cx<R>* n, const double* w,
+                                                           FusedArgs fa, Masks m, int do3b6, cx<R>* src6,
+                                                           cx<R>* gpart, cx<R>* h4part) {
+  using F = Fz<R, N>;
+  constexpr int NN = N * N, KP = F::KP, RB = F::RB;
   constexpr long NR = long(N) * N * N;
-  const long id = long(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (id >= long(T) * NR) return;
-  const int t = int(id / NR);
-  const long r = id - long(t) * NR;
-  double s5 = 0, hr[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
-  for (int q = 0; q < P; ++q) {
-    const cx<R>* b = buf6 + (long(t) * P + q) * 6 * NR + r;
-    const double wq = w[q];
-    const cx<R> pq = psi[long(q) * NR + r];
-    double s = 0;
+  __shared__ cx<R> sm[F::GRP * F::PLANE];
+  const int tid = threadIdx.x;
+  const int x = tid % N, y0 = tid / N;
+  const int c = blockIdx.x % fa.S;
+  const int z = (blockIdx.x / fa.S) % N;
+  const int t = blockIdx.x / (fa.S * N);
+  const int qb = c * fa.chunk, qe = min(fa.P, qb + fa.chunk);
+  const long zo = long(z) * NN + y0 * N + x;      // global offset of owned point i: zo + RB*N*i
+  const int so0 = y0 * F::LD + x;                 // LDS offset of owned point i: so0 + RB*LD*i
+  cx<R> ga[KP][3], h4[KP][3], nk[KP];
 #pragma unroll
-    for (int c = 0; c < 6; ++c) {
-      const cx<R> v = b[c * NR];
-      s += double(v.x) * v.x + double(v.y) * v.y;
-      if (c < 3) {
-        const cx<R> hv = cmulc(v, pq);
-        hr[c] += wq * double(hv.x);
-        hi[c] += wq * double(hv.y);
+  for (int i = 0; i < KP; ++i) {
+#pragma unroll
+    for (int s = 0; s < 3; ++s) ga[i][s] = h4[i][s] = mk<R>(R(0), R(0));
+    nk[i] = n[zo + RB * N * i];
+  }
+  const R a0 = R(-m.m2ax), a1 = R(-m.m2bx1), a2 = R(-m.m3a4);
+  for (int q = qb; q < qe; ++q) {
+    const R wq = R(w[q]);
+    const long pair = long(t) * fa.P + q;
+    for (int c0 = 0; c0 < 7; c0 += F::GRP) {
+      const int nc = min(F::GRP, 7 - c0);
+      for (int cc = 0; cc < nc; ++cc) {
+        const cx<R>* src = buf7 + (pair * 7 + c0 + cc) * NR + zo;
+#pragma unroll
+        for (int i = 0; i < KP; ++i) sm[cc * F::PLANE + so0 + RB * F::LD * i] = src[RB * N * i];
+      }
+      __syncthreads();
+      planes_fft<R, N, 1>(sm, nc, tid);
+#pragma unroll
+      for (int i = 0; i < KP; ++i) {
+        const long r = zo + RB * N * i;
+        const int so = so0 + RB * F::LD * i;
+        const cx<R> pq = psi[long(q) * NR + r];
+#pragma unroll
+        for (int comp = 0; comp < 7; ++comp) {
+          if (comp < c0 || comp >= c0 + nc) continue;
+          cx<R>* slot = sm + (comp - c0) * F::PLANE + so;
+          const cx<R> X = *slot;
+          if (comp == 0) {
+            cfma(ga[i][0], a0 * wq, X, pq);
+          } else if (comp <= 3) {
+            const int cd = comp - 1;
+            cfma(ga[i][1], a1 * wq, X, D[(long(cd) * fa.P + q) * NR + r]);
+            cfma(ga[i][2], a2 * wq, X, H3a4[(long(q) * 3 + cd) * NR + r]);
+            cfma(h4[i][cd], wq, X, pq);
+            *slot = X * nk[i];
+          } else {
+            *slot = X * nk[i];
+          }
+        }
+      }
+      __syncthreads();
+      if (do3b6) {
+        const int s0 = c0 == 0 ? 1 : 0;     // component 0 (XV) has no 3b6 source
+        planes_fft<R, N, -1>(sm + s0 * F::PLANE, nc - s0, tid);
+        for (int cc = s0; cc < nc; ++cc) {
+          cx<R>* dst = src6 + (pair * 6 + c0 + cc - 1) * NR + zo;
+#pragma unroll
+          for (int i = 0; i < KP; ++i) dst[RB * N * i] = sm[cc * F::PLANE + so0 + RB * F::LD * i];
+        }
+        __syncthreads();
       }
     }
-    s5 += wq * s;
   }
-  h5[long(t0 + t) * NR + r] = R(s5);
 #pragma unroll
-  for (int c = 0; c < 3; ++c) H3a4[(long(t0 + t) * 3 + c) * NR + r] = mk<R>(R(hr[c]), R(hi[c]));
+  for (int i = 0; i < KP; ++i) {
+    const long r = zo + RB * N * i;
+#pragma unroll
+    for (int s = 0; s < 3; ++s) {
+      gpart[((long(c) * fa.T + t) * 3 + s) * NR + r] = ga[i][s];
+      h4part[((long(c) * fa.T + t) * 3 + s) * NR + r] = h4[i][s];
+    }
+  }
+}
+
+// One field per pair (xy in G space): partial of coef sum_q w_q Y psi_q.  GRP partners at a time.
+template <typename R, int N>
+__global__ void __launch_bounds__((Fz<R, N>::NTH)) k_fused_Y(const cx<R>* buf1, const cx<R>* psi, const double* w,
+                                                           FusedArgs fa, double coef, cx<R>* gpart) {
+  using F = Fz<R, N>;
+  constexpr int NN = N * N, KP = F::KP, RB = F::RB;
+  constexpr long NR = long(N) * N * N;
+  __shared__ cx<R> sm[F::GRP * F::PLANE];
+  const int tid = threadIdx.x;
+  const int x = tid % N, y0 = tid / N;
+  const int c = blockIdx.x % fa.S;
+  const int z = (blockIdx.x / fa.S) % N;
+  const int t = blockIdx.x / (fa.S * N);
+  const int qb = c * fa.chunk, qe = min(fa.P, qb + fa.chunk);
+  const long zo = long(z) * NN + y0 * N + x;
+  const int so0 = y0 * F::LD + x;
+  cx<R> ga[KP];
+#pragma unroll
+  for (int i = 0; i < KP; ++i) ga[i] = mk<R>(R(0), R(0));
+  for (int q0 = qb; q0 < qe; q0 += F::GRP) {
+    const int nq = min(F::GRP, qe - q0);
+    for (int cc = 0; cc < nq; ++cc) {
+      const cx<R>* src = buf1 + (long(t) * fa.P + q0 + cc) * NR + zo;
+#pragma unroll
+      for (int i = 0; i < KP; ++i) sm[cc * F::PLANE + so0 + RB * F::LD * i] = src[RB * N * i];
+    }
+    __syncthreads();
+    planes_fft<R, N, 1>(sm, nq, tid);
+#pragma unroll
+    for (int i = 0; i < KP; ++i) {
+      const long r = zo + RB * N * i;
+      const int so = so0 + RB * F::LD * i;
+#pragma unroll
+      for (int cc = 0; cc < F::GRP; ++cc) {
+        if (cc >= nq) continue;
+        cfma(ga[i], R(coef * w[q0 + cc]), sm[cc * F::PLANE + so], psi[long(q0 + cc) * NR + r]);
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < KP; ++i) gpart[(long(c) * fa.T + t) * NR + zo + RB * N * i] = ga[i];
+}
+
+// Occupied-occupied pass: buf6 per pair (a = t0+t, b = q) [V_par(3), V_anti(3)], xy in G space.
+//   h5[a]   += w_b (|V_par|^2 + |V_anti|^2)     (Alg. 3a2; TC mode: V_ba = conj(V_ab))
+//   H3a4[a] += w_b conj(V_par) psi_b            (Alg. 3a4 h3; Alg. 3b2 h3 is its conjugate)
+template <typename R, int N>
+__global__ void __launch_bounds__((Fz<R, N>::NTH)) k_fused_O(const cx<R>* buf6, const cx<R>* psi, const double* w,
+                                                           FusedArgs fa, R* h5part, cx<R>* H3part) {
+  using F = Fz<R, N>;
+  constexpr int NN = N * N, KP = F::KP, RB = F::RB;
+  constexpr long NR = long(N) * N * N;
+  __shared__ cx<R> sm[F::GRP * F::PLANE];
+  const int tid = threadIdx.x;
+  const int x = tid % N, y0 = tid / N;
+  const int c = blockIdx.x % fa.S;
+  const int z = (blockIdx.x / fa.S) % N;
+  const int t = blockIdx.x / (fa.S * N);
+  const int qb = c * fa.chunk, qe = min(fa.P, qb + fa.chunk);
+  const long zo = long(z) * NN + y0 * N + x;
+  const int so0 = y0 * F::LD + x;
+  R h5[KP];
+  cx<R> H[KP][3];
+#pragma unroll
+  for (int i = 0; i < KP; ++i) {
+    h5[i] = R(0);
+    H[i][0] = H[i][1] = H[i][2] = mk<R>(R(0), R(0));
+  }
+  for (int q = qb; q < qe; ++q) {
+    const R wq = R(w[q]);
+    const long pair = long(t) * fa.P + q;
+    for (int c0 = 0; c0 < 6; c0 += F::GRP) {
+      const int nc = min(F::GRP, 6 - c0);
+      for (int cc = 0; cc < nc; ++cc) {
+        const cx<R>* src = buf6 + (pair * 6 + c0 + cc) * NR + zo;
+#pragma unroll
+        for (int i = 0; i < KP; ++i) sm[cc * F::PLANE + so0 + RB * F::LD * i] = src[RB * N * i];
+      }
+      __syncthreads();
+      planes_fft<R, N, 1>(sm, nc, tid);
+#pragma unroll
+      for (int i = 0; i < KP; ++i) {
+        const long r = zo + RB * N * i;
+        const int so = so0 + RB * F::LD * i;
+        const cx<R> pq = psi[long(q) * NR + r];
+#pragma unroll
+        for (int comp = 0; comp < 6; ++comp) {
+          if (comp < c0 || comp >= c0 + nc) continue;
+          const cx<R> V = sm[(comp - c0) * F::PLANE + so];
+          h5[i] += wq * (V.x * V.x + V.y * V.y);
+          if (comp < 3) {
+            const cx<R> hv = cmulc(V, pq);
+            H[i][comp].x += wq * hv.x;
+            H[i][comp].y += wq * hv.y;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < KP; ++i) {
+    const long r = zo + RB * N * i;
+    h5part[(long(c) * fa.T + t) * NR + r] = h5[i];
+#pragma unroll
+    for (int cd = 0; cd < 3; ++cd) H3part[((long(c) * fa.T + t) * 3 + cd) * NR + r] = H[i][cd];
+  }
+}
+
+// Sum of the partner-chunk partials in a fixed order (FP64).
+//   mode 0 (occ): h5[t0+t] = sum_c h5part, H3a4[t0+t] = sum_c H3part                  (working precision)
+//   mode 1 (A)  : acc[s][t] += sum_c gpart[c][t][s] (s = 0,1,2), h4[t] = sum_c h4part
+//   mode 2 (Y)  : acc[slot][t] += sum_c gpart[c][t]
+template <typename R, int N>
+__global__ void k_sum_parts(int mode, int S, int T, int t0, int slot, const R* h5part, const cx<R>* H3part,
+                            const cx<R>* gpart, const cx<R>* h4part, R* h5, cx<R>* H3a4, cx<double>* acc, cx<R>* h4) {
+  constexpr long NR = long(N) * N * N;
+  const long id = long(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (id >= long(T) * NR) return;
+  const int t = int(id / NR);
+  const long r = id - long(t) * NR;
+  if (mode == 0) {
+    double s = 0;
+    cx<double> H[3] = {{0, 0}, {0, 0}, {0, 0}};
+    for (int c = 0; c < S; ++c) {
+      s += double(h5part[(long(c) * T + t) * NR + r]);
+#pragma unroll
+      for (int cd = 0; cd < 3; ++cd) {
+        const cx<R> v = H3part[((long(c) * T + t) * 3 + cd) * NR + r];
+        H[cd].x += double(v.x);
+        H[cd].y += double(v.y);
+      }
+    }
+    h5[long(t0 + t) * NR + r] = R(s);
+#pragma unroll
+    for (int cd = 0; cd < 3; ++cd) H3a4[(long(t0 + t) * 3 + cd) * NR + r] = mk<R>(R(H[cd].x), R(H[cd].y));
+  } else if (mode == 1) {
+    cx<double> g[3] = {{0, 0}, {0, 0}, {0, 0}}, h[3] = {{0, 0}, {0, 0}, {0, 0}};
+    for (int c = 0; c < S; ++c) {
+#pragma unroll
+      for (int s = 0; s < 3; ++s) {
+        const cx<R> v = gpart[((long(c) * T + t) * 3 + s) * NR + r];
+        const cx<R> u = h4part[((long(c) * T + t) * 3 + s) * NR + r];
+        g[s].x += double(v.x);
+        g[s].y += double(v.y);
+        h[s].x += double(u.x);
+        h[s].y += double(u.y);
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < 3; ++s) {
+      cx<double>& a = acc[(long(s) * T + t) * NR + r];
+      a.x += g[s].x;
+      a.y += g[s].y;
+      h4[(long(t) * 3 + s) * NR + r] = mk<R>(R(h[s].x), R(h[s].y));
+    }
+  } else {
+    cx<double> g = {0, 0};
+    for (int c = 0; c < S; ++c) {
+      const cx<R> v = gpart[(long(c) * T + t) * NR + r];
+      g.x += double(v.x);
+      g.y += double(v.y);
+    }
+    cx<double>& a = acc[(long(slot) * T + t) * NR + r];
+    a.x += g.x;
+    a.y += g.y;
+  }
+}
+
+// Local (Hartree-type) terms added to the FP64 accumulators, then g_t = sum of the four slots.
+// loc: [VH, h1 x3, P2bh2, F3b1, h6, F3b2]; D is stored component-major D[(c*P + p)*N^3 + r].
+// acc slots: 0 = 2ah/2ax, 1 = 2bh1/2bx1, 2 = other three-body terms, 3 = pass B + 2bh2.
+template <typename R, int N>
+__global__ void k_local(const cx<R>* psi, const cx<R>* D, const cx<R>* loc, const cx<R>* h4, int t0, int T, int P,
+                        Masks m, cx<double>* acc, cx<R>* g) {
+  constexpr long NR = long(N) * N * N;
+  const long id = long(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (id >= long(T) * NR) return;
+  const int t = int(id / NR);
+  const long r = id - long(t) * NR;
+  const long j = t0 + t;
+  const long TS = long(T) * NR;
+  const cx<R> pj = psi[j * NR + r];
+  const cx<R> VH = loc[r];
+  cx<R> h1[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) h1[c] = loc[(1 + c) * NR + r];
+  const cx<R> P2 = loc[4 * NR + r], F3b1 = loc[5 * NR + r], h6 = loc[6 * NR + r], F3b2 = loc[7 * NR + r];
+  cx<R> hD = mk<R>(R(0), R(0)), hh = mk<R>(R(0), R(0)), h14 = mk<R>(R(0), R(0));
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    hD = hD + h1[c] * D[(long(c) * P + j) * NR + r];
+    hh = hh + h1[c] * h1[c];
+    h14 = h14 + h1[c] * h4[(long(t) * 3 + c) * NR + r];
+  }
+  const cx<R> s3 = R(-0.5 * m.m3a1) * hh - R(m.m3b1) * F3b1 + R(0.5 * m.m3a2) * h6 + R(m.m3b2) * F3b2;
+  const cx<R> v[4] = {(R(m.m2ah) * VH) * pj, R(m.m2bh1) * hD, s3 * pj + R(m.m3a3) * h14, (R(m.m2bh2) * P2) * pj};
+  double gx = 0, gy = 0;
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    cx<double>& a = acc[s * TS + long(t) * NR + r];
+    a.x += double(v[s].x);
+    a.y += double(v[s].y);
+    gx += a.x;
+    gy += a.y;
+  }
+  g[long(t) * NR + r] = mk<R>(R(gx), R(gy));
+}
+
+// Energy partials: e[j*4 + slot] = Re sum_r conj(psi_j) acc_slot,t / N^3 (deterministic tree, one block per (t, slot))
+template <typename R, int N>
+__global__ void __launch_bounds__(256) k_epart(const cx<R>* psi, const cx<double>* acc, int t0, int T, double* e) {
+  constexpr long NR = long(N) * N * N;
+  const int t = blockIdx.x / 4, slot = blockIdx.x % 4;
+  const cx<R>* p = psi + long(t0 + t) * NR;
+  const cx<double>* a = acc + (long(slot) * T + t) * NR;
+  double s = 0;
+  for (long r = threadIdx.x; r < NR; r += blockDim.x) s += double(p[r].x) * a[r].x + double(p[r].y) * a[r].y;
+  __shared__ double red[256];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int h = blockDim.x / 2; h > 0; h >>= 1) {
+    if (int(threadIdx.x) < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) e[long(t0 + t) * 4 + slot] = red[0] / double(NR);
 }
 
 // h6 = sum_a w_a h5[a];  M_c = sum_a w_a conj(H3a4[a]_c) psi_a  (H3b = conj(H3a4) in TC mode)
@@ -574,69 +827,6 @@ __global__ void k_passB_Z(const cx<R>* psi, const cx<R>* D, const cx<R>* h1, con
     v = v + R(m.m3b4) * h4[(long(t) * 3 + c) * NR + r];
     Z[(long(t) * 3 + c) * NR + r] = v;
   }
-}
-
-// Local (Hartree-type) terms, then g_t = sum of the four accumulators (working precision).
-// D is stored component-major: D[(c*P + p)*N^3 + r].
-// loc: [VH, h1 x3, P2bh2, F3b1, h6, F3b2] real-space fields
-template <typename R, int N>
-__global__ void k_local(const cx<R>* psi, const cx<R>* D, const cx<R>* loc, const cx<R>* h4, int t0, int T, int P,
-                        Masks m, cx<double>* acc, cx<R>* g) {
-  constexpr long NR = long(N) * N * N;
-  const long id = long(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (id >= long(T) * NR) return;
-  const int t = int(id / NR);
-  const long r = id - long(t) * NR;
-  const long j = t0 + t;
-  const long TS = long(T) * NR;
-  const cx<R> pj = psi[j * NR + r];
-  const cx<R> VH = loc[r];
-  cx<R> h1[3];
-#pragma unroll
-  for (int c = 0; c < 3; ++c) h1[c] = loc[(1 + c) * NR + r];
-  const cx<R> P2 = loc[4 * NR + r], F3b1 = loc[5 * NR + r], h6 = loc[6 * NR + r], F3b2 = loc[7 * NR + r];
-  cx<R> hD = mk<R>(R(0), R(0)), hh = mk<R>(R(0), R(0)), h14 = mk<R>(R(0), R(0));
-#pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    hD = hD + h1[c] * D[(long(c) * P + j) * NR + r];
-    hh = hh + h1[c] * h1[c];
-    h14 = h14 + h1[c] * h4[(long(t) * 3 + c) * NR + r];
-  }
-  const cx<R> s3 = R(-0.5 * m.m3a1) * hh - R(m.m3b1) * F3b1 + R(0.5 * m.m3a2) * h6 + R(m.m3b2) * F3b2;
-  const cx<R> t0v = (R(m.m2ah) * VH) * pj;
-  const cx<R> t1v = R(m.m2bh1) * hD;
-  const cx<R> t3v = (R(m.m2bh2) * P2) * pj;
-  const cx<R> t2v = s3 * pj + R(m.m3a3) * h14;
-  cx<double>* A = acc + long(t) * NR + r;
-  A[0].x += t0v.x; A[0].y += t0v.y;
-  A[TS].x += t1v.x; A[TS].y += t1v.y;
-  A[2 * TS].x += t2v.x; A[2 * TS].y += t2v.y;
-  A[3 * TS].x += t3v.x; A[3 * TS].y += t3v.y;
-  const double gx = A[0].x + A[TS].x + A[2 * TS].x + A[3 * TS].x;
-  const double gy = A[0].y + A[TS].y + A[2 * TS].y + A[3 * TS].y;
-  g[long(t) * NR + r] = mk<R>(R(gx), R(gy));
-}
-
-// Energy partials: e[(j)*4 + slot] = sum_r conj(psi_j) acc_slot,t / N^3 (deterministic tree, one block per (t, slot))
-template <typename R, int N>
-__global__ void __launch_bounds__(256) k_epart(const cx<R>* psi, const cx<double>* acc, int t0, int T, double* e) {
-  constexpr long NR = long(N) * N * N;
-  const int t = blockIdx.x / 4, slot = blockIdx.x % 4;
-  const cx<R>* p = psi + long(t0 + t) * NR;
-  const cx<double>* a = acc + (long(slot) * T + t) * NR;
-  double s = 0;
-  for (long r = threadIdx.x; r < NR; r += blockDim.x) {
-    const double pr = p[r].x, pi = p[r].y;
-    s += pr * a[r].x + pi * a[r].y;   // Re(conj(psi) acc)
-  }
-  __shared__ double red[256];
-  red[threadIdx.x] = s;
-  __syncthreads();
-  for (int h = blockDim.x / 2; h > 0; h >>= 1) {
-    if (int(threadIdx.x) < h) red[threadIdx.x] += red[threadIdx.x + h];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) e[long(t0 + t) * 4 + slot] = red[0] / double(NR);
 }
 
 }  // namespace tcmi
