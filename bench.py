@@ -27,6 +27,29 @@ sys.path.insert(0, HERE)
 METRIC = "orbital-pair TC applications/sec + TC energy error vs FP64 oracle (FP32 vs FP64)"
 HBM_PEAK_GBS = 8000.0
 
+# HBM bytes per launch of a kernel, from two rocprofv3 counter passes (FETCH_SIZE, then WRITE_SIZE) over
+# one bench step, each scaled by what the counter reads for a plain 1 GiB device copy (FETCH x2, WRITE x1),
+# averaged over the launches of the step.  Keyed by kernel and by the hash of the library sources the
+# counters were taken on: any later change to those sources makes the figure stale (reported as null).
+MEASURED_TRAFFIC = {
+    ("k_fused_A<float,24>", "94c57ccc4d7a2b61"): 1.0379e10,
+}
+
+
+def source_hash() -> str:
+    """sha256 (16 hex) of the library's device/host sources and its C header, in file-name order."""
+    import hashlib
+
+    h = hashlib.sha256()
+    d = os.path.join(HERE, "paper_2302_07420_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".hip", ".hpp", ".h")):
+            with open(os.path.join(d, f), "rb") as fh:
+                h.update(fh.read())
+    with open(os.path.join(HERE, "include", "tcmi.h"), "rb") as fh:
+        h.update(fh.read())
+    return h.hexdigest()[:16]
+
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
@@ -105,7 +128,7 @@ def cpu_baseline(budget_s: float):
         "unit": "orbital-pair TC applications/s",
         "cores": torch.get_num_threads(),
         "kind": "oracle",
-        "sample": f"config-2 cell, 24^3 grid, 4 bands, 2x2x2 k-mesh ({npairs} same-spin pairs, all terms, "
+        "sample": f"fcc a=10.26 bohr cell, 24^3 grid, 4 bands, 2x2x2 k-mesh ({npairs} same-spin pairs, all terms, "
                   f"both spins, energy {E:.10f} Ha); {dt:.1f} s",
         "seconds": dt,
     }
@@ -118,7 +141,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 GPU path")
-    ap.add_argument("--config", type=int, default=2, help="workload: 1, 2 (default), 3 or 4")
+    ap.add_argument("--workload", default="fcc_si_k444_g24",
+                    help="named workload: fcc_si_k444_g24 (default), heg14_g16, heg54_twist2_g32, fcc_si_x2_k222_g48")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB first (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -131,7 +155,7 @@ def main():
     import tcinputs as T
     import paper_2302_07420_amd as tc
 
-    w = T.config(args.config)
+    w = T.workload(args.workload)
     log(f"workload {w.name}: nk={w.nk} nb={w.nband} grid={w.grid} pairs={w.npairs}")
     side = torch.cuda.Stream()          # default priority; the library enqueues on this stream
     torch.cuda.set_stream(side)
@@ -170,10 +194,12 @@ def main():
     avg_bytes = st["bytes"] / max(1, st["launches"])
     achieved = avg_bytes / (avg_ms * 1e-3) / 1e9
     total_kernel_ms = sum(v["ms"] for v in stats.values()) / args.steps
+    kname = name.replace("<R,N", "<float,%d" % w.grid[0])
+    shash = source_hash()
     roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None, "kernel": name.replace("<R,N", "<float,%d" % w.grid[0]),
+            "traffic": MEASURED_TRAFFIC.get((kname, shash)) if args.workload == "fcc_si_k444_g24" else None, "kernel": kname,
             "avg_launch_ms": avg_ms, "algorithmic_bytes_per_launch": avg_bytes,
-            "launches_per_step": st["launches"] / args.steps}
+            "launches_per_step": st["launches"] / args.steps, "source_hash": shash}
     per_kernel = {k: {"ms_per_step": v["ms"] / args.steps,
                       "GBps": (v["bytes"] / (v["ms"] * 1e-3) / 1e9) if v["ms"] > 0 and v["bytes"] > 0 else None}
                   for k, v in stats.items() if v["ms"] > 0}

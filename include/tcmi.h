@@ -2,7 +2,7 @@
  *
  * The library applies the two- and three-body terms of the transcorrelated
  * (TC) effective one-body operator h of arXiv:2302.07420 (Sec. 2.1, Eq. SCF;
- * terms of Sec. 2.6.2-2.6.4) to every occupied orbital of a spin-unpolarized
+ * terms of Secs. 2.6.3-2.6.4) to every occupied orbital of a spin-unpolarized
  * plane-wave problem on a uniform Gamma-centred k-mesh, by the FFT pair-density
  * route of the paper's algorithms (Algs. 2ah, 2ax, 3a1-3a4, 3b1-3b6) with the
  * Gygi-Baldereschi divergence corrections for k-points on the SCF mesh
@@ -174,15 +174,15 @@ enum {
   TC_K_FFT_Z_INV = 4,   /* k_fft_z<R,N,+1>                                               */
   TC_K_XY_PAIR_OCC = 5, /* k_xy_pair<R,N,true>: occupied-occupied pair densities, fwd xy */
   TC_K_XY_PAIR_TGT = 6, /* k_xy_pair<R,N,false>: target-partner pair densities, fwd xy  */
-  TC_K_XY_3B6 = 7,      /* k_xy_3b6: 3b6 sources X^U n, fwd xy                          */
+  TC_K_SUM_PARTS = 7,   /* k_sum_parts: fixed-order sums of the partner-chunk partials  */
   TC_K_XY_PASSB = 8,    /* k_xy_passB: pass-B sources, fwd xy                           */
   TC_K_ZCONV_OCC = 9,   /* k_zconv<R,N,OP_O>                                            */
   TC_K_ZCONV_A1 = 10,   /* k_zconv<R,N,OP_A1>                                           */
   TC_K_ZCONV_A2 = 11,   /* k_zconv<R,N,OP_A2>                                           */
   TC_K_ZCONV_B = 12,    /* k_zconv<R,N,OP_B>                                            */
-  TC_K_ACC_OCC = 13,    /* k_acc_O: FP64 partner sums of the occupied-occupied pass     */
-  TC_K_ACC_A1 = 14,     /* k_acc_A1: FP64 partner sums of pass A                        */
-  TC_K_ACC_Y = 15,      /* k_acc_Y: FP64 partner sums of the 3b6 chain and pass B       */
+  TC_K_FUSED_O = 13,    /* k_fused_O: inverse xy + partner sums, occupied-occupied pass */
+  TC_K_FUSED_A = 14,    /* k_fused_A: inverse xy + partner sums of pass A, 3b6 sources  */
+  TC_K_FUSED_Y = 15,    /* k_fused_Y: inverse xy + partner sums, 3b6 chain and pass B   */
   TC_K_OTHER = 16,      /* densities, Hartree-type fields, local terms, gathers          */
   TC_K_CORR = 17,       /* FP64 corrections, overlaps and kinetic energy                 */
   TC_K_NKERNEL = 18

@@ -8,7 +8,7 @@ same seeded inputs from ``tcinputs``.
 
 Modules
   fftroute  the operator evaluated term by term following the paper's
-            algorithms (Sec. 2.6.2, Algs. 2ah/2ax/3a1-3a4/3b1-3b6) with the
+            algorithms (Secs. 2.6.3-2.6.4, Algs. 2ah/2ax/3a1-3a4/3b1-3b6) with the
             Gygi-Baldereschi corrections (Sec. 2.5 and the per-term equations),
             the pseudo-energy (Eqs. EtotTC / EtotBiTC) and its autograd gradient.
   brute     the same discrete quantities as literal real-space double and triple

@@ -34,7 +34,7 @@ from .fftroute import jastrow_kernels
 FOURPI = 4.0 * math.pi
 
 # (name, sign, permutation of (j, q1, q2) into kets at (x1, x2, x3)); the sign
-# is the determinant sign times the overall -1/2 of Eq. SCF, as listed in Sec. 2.6.3.
+# is the determinant sign times the overall -1/2 of Eq. SCF, as listed in Sec. 2.6.4.
 PERMS = [
     ("1", -0.5, (0, 1, 2)),
     ("2", +0.5, (0, 2, 1)),

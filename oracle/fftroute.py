@@ -5,16 +5,16 @@ float64/complex128; ``torch.fft`` is used as a library primitive for the
 periodic Fourier transform FT and its inverse.  Nothing is fused or reordered
 beyond the paper's own algorithms; each term is computed separately.
 
-Conventions (restating the paper's Secs. 2.2-2.4 in the units used here)
+Conventions (restating the paper's Secs. 2.2, 2.3 and 2.6 in the units used here)
   * FT[f](G) = (1/N_r) sum_r f(r) e^{-iG.r}  (periodic transform, Sec. 2.2,
     evaluated on the real-space grid), FT^{-1}[F](r) = sum_G F(G) e^{iG.r};
   * the kernels are the non-periodic transforms of Sec. 2.2 (FT(1/r) = 4pi/G^2,
-    the Jastrow transforms of Sec. 2.6.2 and Appendix B);
+    the Jastrow transforms of Sec. 2.6.3 and Appendix B);
   * a kernel applied to a Bloch pair density with crystal momentum Delta is
     sum_G K(Delta+G) FT[rho](G) e^{iG.r} (Eq. convolution), Delta = k_target -
     k_partner exactly as written in the algorithms (not reduced modulo G);
   * orbitals: physical cell-periodic parts phi(r) = Omega^{-1/2} sum c(G) e^{iG.r}
-    (Sec. 2.3; the paper's dimensionless arrays are sqrt(Omega) phi and their
+    (Secs. 2.3 and 2.6.1; the paper's dimensionless arrays are sqrt(Omega) phi and their
     1/Omega factors are restored here);
   * g_j(r) is the cell-periodic part of a term applied to phi_j, with the
     weights f_q / N_k of the algorithms.
@@ -37,7 +37,7 @@ Readings where the paper is silent or garbled (each restated in the design doc):
   R7  The three-body total is 3a1 + 3a2 + 2 3a3 + 2 3a4 + 2 (3b1+...+3b6)
       (3a5 = 3a4, 3a6 = 3a3, 3c* = 3b*), checked by the brute-force oracle.
   R9  Alg. 3b5 ends with g_j <- g_j - (1/2) h5 phi_q2 f/N_k: the printed "+" contradicts
-      the caption of Alg. 3b5, the term list of Sec. 2.6.3 (-1/2) and Eq. 3b5_div; the
+      the caption of Alg. 3b5, the term list of Sec. 2.6.4 (-1/2) and Eq. 3b5_div; the
       literal permutation integral of the brute-force oracle fixes the sign.
   R8  Energy: E = (1/N_k) Re sum_{sigma,k,mu} f <chi| T + h2/2 + h3/3 |phi> per
       cell, which equals Eq. EtotBiTC for biorthonormal determinants.
@@ -82,7 +82,7 @@ def w_closed(g):
 def jastrow_kernels(Q2: torch.Tensor, A, C):
     """u~, laplacian-u~ and (grad u)^2~ of u = A/r (1 - exp(-r/C)) at |Q|^2 = Q2 > 0.
 
-    Sec. 2.6.2: u~ = 4 pi A (1/Q^2 - 1/(Q^2 + C^-2)), (lap u)~ = -Q^2 u~,
+    Sec. 2.6.3: u~ = 4 pi A (1/Q^2 - 1/(Q^2 + C^-2)), (lap u)~ = -Q^2 u~,
     (grad u)^2~ = (4 pi A^2/(C g)) [-(pi/4) g^2 - (1+g^2/2) atan(g/2) + (1+g^2) atan g],
     g = C Q.  Q2 must be strictly positive (callers mask Q = 0).
     """
@@ -584,7 +584,7 @@ class Problem:
         return self.omega * torch.mean(torch.conj(o["chi"]) * g, dim=(-3, -2, -1))
 
     def kinetic(self):
-        """<chi_p| -nabla^2/2 |phi_p> from the coefficients (Sec. 2.6.1)."""
+        """<chi_p| -nabla^2/2 |phi_p> from the coefficients (Sec. 2.6.2)."""
         out = []
         for ik in range(self.nk):
             kg = (self.kfrac[ik][None, :] + self.miller[ik]) @ self.B

@@ -4,7 +4,7 @@ TEST INFRASTRUCTURE ONLY.  NumPy float64, no grid and no FFT.  When every
 occupied orbital is a single plane wave e^{i p.r} (p = k + G), every pair
 density has one Fourier component, FT[chi*_q phi_j] = delta_{G, G_j - G_q}/Omega,
 so each term of Sec. 2.6 is diagonal, g_j = eps_j phi_j, with eps_j a finite
-sum over occupied momenta of the analytic kernels (Sec. 2.6.2, Appendix B).
+sum over occupied momenta of the analytic kernels (Sec. 2.6.3, Appendix B).
 Densities are uniform, so every Hartree-type term (2ah, 2bh1, 2bh2, 3a1, 3a3,
 3b1, 3b2, 3b3) vanishes (G = 0 is dropped).  Valid while the FFT grid does not
 alias the pair densities.  Kernel values at Q = 0 follow the same readings as

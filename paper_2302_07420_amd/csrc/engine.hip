@@ -44,7 +44,7 @@ struct TcError {
 };
 
 // ------------------------------------------------------------------ kernels of u = A/r (1 - e^{-r/C})
-// Fourier transforms of Sec. 2.6.2 and Appendix B (non-periodic convention).
+// Fourier transforms of Sec. 2.6.3 and Appendix B (non-periodic convention).
 struct Jk {
   double u, lap, w;
 };
@@ -701,11 +701,11 @@ struct EngineT : Engine {
           hipLaunchKernelGGL((k_zconv<R, N, OP_O>), dim3(nblk(npair * N * N)), dim3(256), 0, s, bufA.p, bufB.p,
                              npair, a0, mi, rc, tb, 0);
         });
-        K(TC_K_ACC_OCC, fb * (6.0 * npair + P) + 4.0 * fb * nt * S, [&] {
+        K(TC_K_FUSED_O, fb * (6.0 * npair + P) + 4.0 * fb * nt * S, [&] {
           hipLaunchKernelGGL((k_fused_O<R, N>), dim3(unsigned(nt) * N * S), dim3(Fz<R, N>::NTH), 0, s, bufB.p, psi.p,
                              sh.w.p, fa, h5part.p, H3part.p);
         });
-        K(TC_K_OTHER, 4.0 * fb * nt * (S + 1), [&] {
+        K(TC_K_SUM_PARTS, 4.0 * fb * nt * (S + 1), [&] {
           hipLaunchKernelGGL((k_sum_parts<R, N>), dim3(nblk(long(nt) * NR)), dim3(256), 0, s, 0, S, nt, a0, 0,
                              h5part.p, H3part.p, nullptr, nullptr, h5.p, H3a4.p, nullptr, nullptr);
         });
@@ -749,11 +749,11 @@ struct EngineT : Engine {
                              npair, t0, mi, rc, tb, 1);
         });
         const FusedArgs fa{P, nt, t0, S, chunk};
-        K(TC_K_ACC_A1, fb * ((m.m3b6 ? 13.0 : 7.0) * npair + 8.0 * P + nt) + 6.0 * part, [&] {
+        K(TC_K_FUSED_A, fb * ((m.m3b6 ? 13.0 : 7.0) * npair + 8.0 * P + nt) + 6.0 * part, [&] {
           hipLaunchKernelGGL((k_fused_A<R, N>), dim3(unsigned(nt) * N * S), dim3(Fz<R, N>::NTH), 0, s, bufB.p, psi.p,
                              D.p, H3a4.p, nJ.p, sh.w.p, fa, m, int(m.m3b6 != 0), bufA.p, gpart.p, h4part.p);
         });
-        K(TC_K_OTHER, 6.0 * part + 6.0 * fd * nt + 3.0 * fb * nt, [&] {
+        K(TC_K_SUM_PARTS, 6.0 * part + 6.0 * fd * nt + 3.0 * fb * nt, [&] {
           hipLaunchKernelGGL((k_sum_parts<R, N>), dim3(nblk(long(nt) * NR)), dim3(256), 0, s, 1, S, nt, t0, 0, nullptr,
                              nullptr, gpart.p, h4part.p, nullptr, nullptr, acc.p, h4.p);
         });
@@ -762,11 +762,11 @@ struct EngineT : Engine {
             hipLaunchKernelGGL((k_zconv<R, N, OP_A2>), dim3(nblk(npair * N * N)), dim3(256), 0, s, bufA.p, bufB.p,
                                npair, t0, mi, rc, tb, 1);
           });
-          K(TC_K_ACC_Y, fb * (npair + P) + part, [&] {
+          K(TC_K_FUSED_Y, fb * (npair + P) + part, [&] {
             hipLaunchKernelGGL((k_fused_Y<R, N>), dim3(unsigned(nt) * N * S), dim3(Fz<R, N>::NTH), 0, s, bufB.p,
                                psi.p, sh.w.p, fa, 1.0, gpart.p);
           });
-          K(TC_K_OTHER, part + 2.0 * fd * nt, [&] {
+          K(TC_K_SUM_PARTS, part + 2.0 * fd * nt, [&] {
             hipLaunchKernelGGL((k_sum_parts<R, N>), dim3(nblk(long(nt) * NR)), dim3(256), 0, s, 2, S, nt, t0, 2,
                                nullptr, nullptr, gpart.p, nullptr, nullptr, nullptr, acc.p, nullptr);
           });
@@ -788,11 +788,11 @@ struct EngineT : Engine {
                              npair, t0, mi, rc, tb, 1);
         });
         const FusedArgs fy{P, nt, t0, S, chunk};
-        K(TC_K_ACC_Y, fb * (npair + P) + part, [&] {
+        K(TC_K_FUSED_Y, fb * (npair + P) + part, [&] {
           hipLaunchKernelGGL((k_fused_Y<R, N>), dim3(unsigned(nt) * N * S), dim3(Fz<R, N>::NTH), 0, s, bufB.p, psi.p,
                              sh.w.p, fy, 1.0, gpart.p);
         });
-        K(TC_K_OTHER, part + 2.0 * fd * nt, [&] {
+        K(TC_K_SUM_PARTS, part + 2.0 * fd * nt, [&] {
           hipLaunchKernelGGL((k_sum_parts<R, N>), dim3(nblk(long(nt) * NR)), dim3(256), 0, s, 2, S, nt, t0, 3, nullptr,
                              nullptr, gpart.p, nullptr, nullptr, nullptr, acc.p, nullptr);
         });

@@ -224,17 +224,21 @@ def fcc_si(kmesh=(4, 4, 4), grid=24, ecut=8.14, nb=4, a=10.26, supercell=1,
                     mill, right, left, occs, (A, A), cusp_C(A), 10.0 / kc ** 2, nelec)
 
 
-def config(i: int) -> Workload:
-    """The five named workloads (1-based), at full size."""
-    if i == 1:
-        return heg_gamma()
-    if i == 2 or i == 5:
-        return fcc_si()
-    if i == 3:
-        return heg_twist()
-    if i == 4:
-        return fcc_si(kmesh=(2, 2, 2), grid=48, nb=32, supercell=2, seed_offset=4)
-    raise ValueError(i)
+WORKLOADS = {
+    # 14-electron gas at r_s = 4, Gamma only, 7 occupied plane waves, 16^3 grid (49 pairs)
+    "heg14_g16": heg_gamma,
+    # fcc a = 10.26 bohr, 4x4x4 k-mesh, 4 bands, ~300 plane waves, 24^3 grid (65,536 pairs)
+    "fcc_si_k444_g24": fcc_si,
+    # 54-electron gas at r_s = 2, 2x2x2 twists, 27 bands, 32^3 grid (46,656 pairs)
+    "heg54_twist2_g32": heg_twist,
+    # 2x2x2 supercell of the fcc cell, 2x2x2 k-mesh, 32 bands, ~2400 plane waves, 48^3 grid (65,536 pairs)
+    "fcc_si_x2_k222_g48": lambda: fcc_si(kmesh=(2, 2, 2), grid=48, nb=32, supercell=2, seed_offset=4),
+}
+
+
+def workload(name: str) -> Workload:
+    """A named full-size workload (see WORKLOADS)."""
+    return WORKLOADS[name]()
 
 
 def tiny_fcc(kmesh=(2, 1, 1), grid=8, ecut=1.2, nb=2, a=6.0, seed_offset=100,

@@ -10,7 +10,7 @@ sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 import tcinputs as T  # noqa: E402
 from oracle.heg import gb_delta  # noqa: E402
 
-w = T.config(1)
+w = T.workload("heg14_g16")
 L = float(w.lattice[0, 0])
 d = gb_delta(w.lattice, w.kmesh, w.alpha)
 out = {

@@ -80,7 +80,7 @@ def test_total_and_energy_fp32(case):
 
 
 def test_electron_gas_closed_form_fp64():
-    w = T.config(1)
+    w = T.workload("heg14_g16")
     _say("[gpu] heg14 gamma 16^3 fp64 vs closed forms")
     op = tc.from_workload(w, precision=tc.TC_PREC_FP64)
     Eg, parts = op.energy()
@@ -90,7 +90,7 @@ def test_electron_gas_closed_form_fp64():
 
 
 def test_hartree_fock_limit_fp64():
-    w = T.config(1).replace(A=(0.0, 0.0))
+    w = T.workload("heg14_g16").replace(A=(0.0, 0.0))
     _say("[gpu] heg14 A=0 (Hartree-Fock) fp64")
     op = tc.from_workload(w, precision=tc.TC_PREC_FP64)
     Eg, parts = op.energy()

@@ -7,7 +7,7 @@ from oracle.brute import Brute
 from oracle.fftroute import Problem, TERMS3
 from oracle.heg import heg_energy, heg_terms
 
-# 3c_k equals 3b_{k'} after x2 <-> x3, q1 <-> q2 (Sec. 2.6.3)
+# 3c_k equals 3b_{k'} after x2 <-> x3, q1 <-> q2 (Sec. 2.6.4)
 C_TO_B = {"1": "1", "2": "2", "3": "6", "4": "5", "5": "4", "6": "3"}
 
 
@@ -43,7 +43,7 @@ def test_fftroute_equals_literal_permutation_integrals(w):
 
 
 def test_electron_gas_gamma_every_term_closed_form():
-    w = T.config(1)
+    w = T.workload("heg14_g16")
     E, parts = Problem(w).energy(per_term=True)
     Eh, ph = heg_energy(w)
     for k, v in ph.items():

@@ -59,7 +59,7 @@ def test_w_small_g_branch_and_limits():
 
 def test_gb_madelung_limit_and_hf_closed_form():
     ref = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "heg_hf_exchange.json")))
-    w = T.config(1)
+    w = T.workload("heg14_g16")
     L = w.lattice[0, 0]
     # alpha -> 0: 4 pi Delta_GB / Omega is the simple-cubic Madelung constant / L
     for a in (0.5, 1.0):
