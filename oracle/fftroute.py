@@ -132,6 +132,9 @@ class Problem:
         self.nyq = torch.as_tensor(nyq)
         self.negidx = [torch.as_tensor((-np.arange(N)) % N) for N in self.grid]
         self._kcache: Dict = {}
+        # optional sample of target orbitals: terms are then evaluated for these targets only
+        # (the other rows are returned as zeros); partner sums are untouched
+        self.tsel = None
         # orbitals
         cr = [torch.as_tensor(c, dtype=CD) for c in w.right] if coeff is None else list(coeff)
         if left is not None:
@@ -270,6 +273,18 @@ class Problem:
             return np.arange(self.P)
         return np.nonzero(o["k"] == ik)[0]
 
+    def restrict_targets(self, targets):
+        """Evaluate the operator only on the given target orbitals (sampled checks at full size)."""
+        self.tsel = None if targets is None else np.unique(np.asarray(targets, dtype=np.int64))
+
+    def sel_t(self, s, ik):
+        """Targets at k-point ik (all orbitals of ik unless a target sample is set)."""
+        J = self.sel(s, ik)
+        return J if self.tsel is None else J[np.isin(J, self.tsel)]
+
+    def is_target(self, j):
+        return self.tsel is None or bool(np.isin(j, self.tsel))
+
     def rho0(self, a, b):
         """FT[chi_a^* phi_b](0) = <chi_a|phi_b>/Omega (periodic parts)."""
         return torch.mean(a * b, dim=(-3, -2, -1))
@@ -309,12 +324,15 @@ class Problem:
         acc = {}
         for q in range(self.P):
             for kt in range(self.nk):
-                J = self.sel(s, kt)
+                J = self.sel_t(s, kt)
+                if len(J) == 0:
+                    continue
                 d = self.dk(kt, o["k"][q])
                 contrib = body(q, J, d)
                 for jj, j in enumerate(J):
                     acc[j] = acc.get(j, 0) + contrib[jj]
-        return torch.stack([acc[j] for j in range(self.P)])
+        zero = torch.zeros_like(o["phi"][0])
+        return torch.stack([acc.get(j, zero) for j in range(self.P)])
 
     def t_2ax(self, s):
         """Alg. 2ax (+ Eq. divcorr_2ax_scf)."""
@@ -334,6 +352,9 @@ class Problem:
         o = self.orb[s]
         out = []
         for j in range(self.P):
+            if not self.is_target(j):
+                out.append(torch.zeros_like(o["phi"][0]))
+                continue
             Q = self.sel(s, o["k"][j])
             r0 = self.rho0(torch.conj(o["chi"][Q]), o["phi"][j][None])   # (nb,)
             out.append(-FOURPI * self.delta_gb * torch.sum((o["f"][Q] * r0)[:, None, None, None] * o["phi"][Q], 0))
@@ -421,7 +442,9 @@ class Problem:
     def t_3a3(self, s):
         """Alg. 3a3: g_j = h1 . h4 / 2."""
         h1 = self.h1(s)
-        return torch.stack([0.5 * torch.sum(h1 * self.h4_3a3(s, j), 0) for j in range(self.P)])
+        zero = torch.zeros_like(self.orb[s]["phi"][0])
+        return torch.stack([0.5 * torch.sum(h1 * self.h4_3a3(s, j), 0) if self.is_target(j) else zero
+                            for j in range(self.P)])
 
     def h3_3a4(self, s, q2):
         """h3^{s2}(r; q2) of Alg. 3a4 (q2 of spin s, same-spin partners q1)."""
@@ -440,7 +463,9 @@ class Problem:
         for q2 in range(self.P):
             h3 = self.h3_3a4(s, q2)
             for kt in range(self.nk):
-                J = self.sel(s, kt)
+                J = self.sel_t(s, kt)
+                if len(J) == 0:
+                    continue
                 d = self.dk(kt, o["k"][q2])
                 h5 = self.conv(d, "X", 0, self.FT(torch.conj(o["chi"][q2])[None] * o["phi"][J]), "U")
                 g[J] = g[J] - 0.5 * torch.sum(h3[None] * h5, 1) * o["w"][q2]
@@ -491,6 +516,9 @@ class Problem:
         o = self.orb[s]
         g = []
         for j in range(self.P):
+            if not self.is_target(j):
+                g.append(torch.zeros_like(o["phi"][0]))
+                continue
             h3 = self.h4_3a3(s, j)
             acc = 0
             for q1 in range(self.P):
@@ -508,7 +536,9 @@ class Problem:
         for q2 in range(self.P):
             h3 = self.h3_3b2(s, q2)
             for kt in range(self.nk):
-                J = self.sel(s, kt)
+                J = self.sel_t(s, kt)
+                if len(J) == 0:
+                    continue
                 d = self.dk(kt, o["k"][q2])
                 h4 = h3[None] * o["phi"][J][:, None]
                 h5 = self.conv(d, "X", 0, self.FT(h4), "Ud")
@@ -538,6 +568,9 @@ class Problem:
         o = self.orb[s]
         out = []
         for j in range(self.P):
+            if not self.is_target(j):
+                out.append(torch.zeros_like(o["phi"][0]))
+                continue
             Q = self.sel(s, o["k"][j])
             acc = 0
             for s1 in range(2):

@@ -1,0 +1,129 @@
+"""Parity at full workload sizes, in the launch configuration the benchmark times.
+
+The oracle cannot evaluate every output at these sizes in seconds, so each test
+checks what it can compute independently:
+  * the 54-electron gas on a 2x2x2 twist mesh (216 orbitals, 32^3 grid): every
+    term and every output element against the plane-wave closed forms;
+  * the fcc bench workload (256 orbitals, 24^3 grid) and its 2x2x2 supercell
+    (48^3 grid): sampled target orbitals against the FP64 oracle restricted to
+    those targets, for every term whose oracle cost does not grow with the
+    number of orbital pairs (all but 3a2, 3a4, 3b2, 3b5);
+  * the terms left out there through a property that holds at any size: the
+    three-body block <phi_i|h3|phi_j> is Hermitian, and the V2a block too.
+"""
+import numpy as np
+import pytest
+
+import tcinputs as T
+from oracle.fftroute import MULT, Problem
+from oracle.heg import heg_energy, heg_terms
+
+pytestmark = pytest.mark.gpu
+
+tc = pytest.importorskip("paper_2302_07420_amd")
+
+FP64_TOL = 1e-10
+FP32_TOL = 2e-6
+PAIR_FREE = ("2ah", "2bh1", "2bh2", "2ax", "2bx1", "2bx2", "3a1", "3a3", "3b1", "3b3", "3b4", "3b6")
+THREE_BODY = ("3a1", "3a2", "3a3", "3a4", "3b1", "3b2", "3b3", "3b4", "3b5", "3b6")
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def _mask(terms, corr=True):
+    m = 0
+    for t in terms:
+        m |= tc.TERM_BITS[t]
+    return m | (tc.TERM_BITS["corr"] if corr else 0)
+
+
+def _rows(hc, w, targets):
+    """Output rows of the given flat orbital indices (k-major, then band)."""
+    nb = w.right[0].shape[0]
+    return [hc[j // nb][j % nb] for j in targets]
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", FP64_TOL), ("fp32", FP32_TOL)])
+def test_electron_gas_54_every_element(prec, tol):
+    w = T.workload("heg54_twist2_g32")
+    _say(f"[gpu] heg54 twist2 32^3 {prec}: all terms vs closed forms")
+    eps, p, f = heg_terms(w)
+    lam = sum(MULT.get(t, 1) * e for t, e in eps.items())       # eigenvalue of h2 + h3 per orbital
+    op = tc.from_workload(w, precision=tc.TC_PREC_FP64 if prec == "fp64" else tc.TC_PREC_FP32)
+    hc = op.apply()
+    Eg, _ = op.energy()
+    op.close()
+    nb = w.right[0].shape[0]
+    exp = [lam[ik * nb:(ik + 1) * nb, None] * w.right[ik] for ik in range(w.nk)]
+    scale = max(np.abs(x).max() for x in exp)
+    err = max(np.abs(a - b).max() for a, b in zip(hc, exp)) / scale
+    _say(f"    max element error / max |h c| = {err:.3e}")
+    assert err < tol
+    Eh, _ = heg_energy(w)
+    assert abs(Eg - Eh) < (FP64_TOL if prec == "fp64" else 1e-6) * abs(Eh)
+
+
+def _sampled(w, targets, terms, prec, tol, batch=0):
+    pr = Problem(w)
+    pr.restrict_targets(targets)
+    ref = 0
+    for t in terms:
+        ref = ref + MULT.get(t, 1) * pr.term(t, 0)
+    exp = pr.to_coeff(ref)
+    nb = w.right[0].shape[0]
+    exp_rows = [exp[j // nb][j % nb].numpy() for j in targets]
+    op = tc.from_workload(w, precision=tc.TC_PREC_FP64 if prec == "fp64" else tc.TC_PREC_FP32,
+                          terms=_mask(terms), batch=batch)
+    hc = op.apply()
+    op.close()
+    got = _rows(hc, w, targets)
+    scale = max(np.abs(x).max() for x in exp_rows)
+    err = max(np.abs(a - b).max() for a, b in zip(got, exp_rows)) / scale
+    _say(f"    sampled targets {list(targets)}: max element error / max |h c| = {err:.3e}")
+    assert err < tol
+
+
+@pytest.mark.parametrize("prec,tol", [("fp32", FP32_TOL), ("fp64", FP64_TOL)])
+def test_bench_workload_sampled_targets(prec, tol):
+    w = T.workload("fcc_si_k444_g24")
+    _say(f"[gpu] fcc_si_k444_g24 {prec}: sampled targets vs oracle (pair-free terms)")
+    _sampled(w, [0, 149, 255], PAIR_FREE, prec, tol)
+
+
+def test_supercell_48_sampled_target_fp32():
+    w = T.workload("fcc_si_x2_k222_g48")
+    _say("[gpu] fcc_si_x2_k222_g48 fp32: one sampled target vs oracle (pair-free terms)")
+    _sampled(w, [77], PAIR_FREE, "fp32", FP32_TOL)
+
+
+@pytest.mark.parametrize("part", ["three_body", "v2a"])
+def test_bench_workload_hermitian_blocks_fp64(part):
+    w = T.workload("fcc_si_k444_g24")
+    terms = THREE_BODY if part == "three_body" else ("2ah", "2ax")
+    _say(f"[gpu] fcc_si_k444_g24 fp64: {part} block Hermitian at full size")
+    op = tc.from_workload(w, precision=tc.TC_PREC_FP64, terms=_mask(terms))
+    hc = op.apply()
+    op.close()
+    worst = 0.0
+    for ik in range(w.nk):
+        M = np.conj(w.right[ik]) @ hc[ik].T            # M_ab = <phi_a | h phi_b>
+        worst = max(worst, np.abs(M - M.conj().T).max() / np.abs(M).max())
+    _say(f"    max |M - M^H| / max |M| over k = {worst:.3e}")
+    assert worst < 1e-11
+
+
+def test_bench_workload_fp32_matches_fp64_every_element():
+    w = T.workload("fcc_si_k444_g24")
+    _say("[gpu] fcc_si_k444_g24: all terms, fp32 (bench launch configuration) vs fp64")
+    out = {}
+    for name, prec in (("fp64", tc.TC_PREC_FP64), ("fp32", tc.TC_PREC_FP32)):
+        op = tc.from_workload(w, precision=prec)
+        out[name] = (op.apply(), op.energy()[0])
+        op.close()
+    scale = max(np.abs(x).max() for x in out["fp64"][0])
+    err = max(np.abs(a - b).max() for a, b in zip(out["fp32"][0], out["fp64"][0])) / scale
+    _say(f"    max element difference / max |h c| = {err:.3e}; energies {out['fp32'][1]!r} {out['fp64'][1]!r}")
+    assert err < FP32_TOL
+    assert abs(out["fp32"][1] - out["fp64"][1]) < 1e-6 * abs(out["fp64"][1])

@@ -117,3 +117,14 @@ def test_energy_is_quadratic_in_A():
     X = np.array([[1, a1, a2, a1 * a1, a1 * a2, a2 * a2] for a1, a2 in grid])
     coef, res, *_ = np.linalg.lstsq(X, E, rcond=None)
     assert np.max(np.abs(X @ coef - E)) < 1e-12 * np.max(np.abs(E))
+
+
+def test_target_sample_rows_equal_full_rows():
+    """Restricting the oracle to a sample of targets leaves those rows unchanged (full-size sampled checks)."""
+    w = T.tiny_fcc(kmesh=(2, 2, 1), grid=8, ecut=2.0, nb=2, a=6.0, occ=[1.0, 0.6])
+    full, part = Problem(w), Problem(w)
+    part.restrict_targets([1, 6])
+    for t in ("2ax", "2bx1", "2bx2", "3a3", "3a4", "3b3", "3b4", "3b5", "3b6", "2ah", "3a1"):
+        a, b = full.term(t, 0), part.term(t, 0)
+        for j in (1, 6):
+            assert torch.max(torch.abs(b[j] - a[j])) <= 1e-14 * torch.max(torch.abs(a)), (t, j)
