@@ -143,11 +143,29 @@ int tc_apply_all_dev(tc_ctx* ctx, void* out_dev);
  * e_parts: NULL or TC_E_NPARTS doubles. */
 int tc_energy(tc_ctx* ctx, double* e_total, double* e_parts);
 
-/* Gradient of the pseudo-energy: grad (host, [nk][nband][npw_max] complex128)
- * receives dE/dRe c + i dE/dIm c = 2 dE/dc* for the coefficients shared by both
- * spin channels; dA / dC (may be NULL) receive dE/dA_s and dE/dC_s with the four
- * parameters independent.  Pair densities are recomputed, not stored. */
+/* Gradient of the pseudo-energy of the loaded orbitals (the functional returned by
+ * tc_energy, with the selected terms and corrections).  grad (host, may be NULL)
+ * receives [nk][nband][npw_max] complex128 dE/dRe c + i dE/dIm c = 2 dE/dc* for the
+ * coefficients shared by both spin channels, zero-padded like tc_apply_all; dA and
+ * dC (may be NULL) receive dE/dA_s and dE/dC_s (s = parallel, antiparallel) with the
+ * four parameters independent.  Both are exact derivatives of the discrete energy:
+ * the orbital gradient comes from one extra application whose scalar kernel is
+ * 4 pi/Q^2 - (grad u)^2~ (the Hermitian part of the pair interaction of Eq. V2body,
+ * whose first variation the grad-u . grad terms and their adjoints reduce to) with
+ * the three-body operator of Sec. 2.6.4 unchanged; dA and dC come from energies
+ * along the exact tangents of the kernel tables (Sec. 2.6.3, Appendix B) and of the
+ * correction prefactors (Eqs. u_short, divcor_3a2_first/second, 3b6_div_scf1-3),
+ * on which the energy depends quadratically.  Pair densities are recomputed, not
+ * stored.  Cost: one application for grad, two per requested parameter.
+ * Errors: TC_ERR_ARG if all three outputs are NULL; TC_ERR_UNSUPPORTED unless the
+ * selected terms contain 2bh1, 2bh2, 2bx1, 2bx2 together or none of them (and then
+ * also 2ah and 2ax), and all three-body terms or none.  The energies of the last
+ * tc_apply_all* stay available to tc_energy; its output buffer is not. */
 int tc_energy_backward(tc_ctx* ctx, double* grad, double dA[2], double dC[2]);
+
+/* Same, writing grad to a caller-owned device buffer of the same layout (may be NULL).
+ * Synchronous: returns after the stream has finished the work. */
+int tc_energy_backward_dev(tc_ctx* ctx, void* grad_dev, double dA[2], double dC[2]);
 
 /* Wait for all work queued by this context. */
 int tc_sync(tc_ctx* ctx);

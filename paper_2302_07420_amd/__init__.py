@@ -65,6 +65,7 @@ def lib():
         "tc_apply_all_dev": (I, [P, P]),
         "tc_energy": (I, [P, dp, dp]),
         "tc_energy_backward": (I, [P, dp, dp, dp]),
+        "tc_energy_backward_dev": (I, [P, P, dp, dp]),
         "tc_sync": (I, [P]),
         "tc_last_timing": (I, [P, dp, dp, I]),
         "tc_set_batch": (I, [P, I]),
@@ -176,14 +177,25 @@ class TCOperator:
         self._check(self._L.tc_energy(self._h, _dp(e), _dp(parts)), "tc_energy")
         return float(e[0]), dict(zip(E_PARTS, parts.tolist()))
 
-    def backward(self):
+    def backward(self, want_grad=True, want_params=True):
+        """(grad per k as (nband, npw) complex128 = 2 dE/dc*, dE/dA (2,), dE/dC (2,)); unrequested parts are None."""
         nk = len(self.npw)
-        g = np.zeros((nk, self.nband, self.npw_max), dtype=np.complex128)
-        dA = np.zeros(2)
-        dC = np.zeros(2)
-        self._check(self._L.tc_energy_backward(self._h, _dp(g.view(np.float64)), _dp(dA), _dp(dC)),
+        g = np.zeros((nk, self.nband, self.npw_max), dtype=np.complex128) if want_grad else None
+        dA = np.zeros(2) if want_params else None
+        dC = np.zeros(2) if want_params else None
+        self._check(self._L.tc_energy_backward(self._h, _dp(g.view(np.float64)) if want_grad else None,
+                                               _dp(dA) if want_params else None, _dp(dC) if want_params else None),
                     "tc_energy_backward")
-        return [g[k, :, : self.npw[k]] for k in range(nk)], dA, dC
+        return ([g[k, :, : self.npw[k]] for k in range(nk)] if want_grad else None), dA, dC
+
+    def backward_dev(self, grad_ptr: Optional[int], want_params=True):
+        """Gradient into a device buffer [nk][nband][npw_max] complex128; returns (dE/dA, dE/dC) or (None, None)."""
+        dA = np.zeros(2) if want_params else None
+        dC = np.zeros(2) if want_params else None
+        self._check(self._L.tc_energy_backward_dev(self._h, ctypes.c_void_p(grad_ptr) if grad_ptr else None,
+                                                   _dp(dA) if want_params else None,
+                                                   _dp(dC) if want_params else None), "tc_energy_backward_dev")
+        return dA, dC
 
     def sync(self):
         self._check(self._L.tc_sync(self._h), "tc_sync")

@@ -17,6 +17,7 @@
 #include <cstring>
 #include <memory>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/tcmi.h"
@@ -45,25 +46,87 @@ struct TcError {
 
 // ------------------------------------------------------------------ kernels of u = A/r (1 - e^{-r/C})
 // Fourier transforms of Sec. 2.6.3 and Appendix B (non-periodic convention).
-struct Jk {
-  double u, lap, w;
+// Forward-mode derivative: value v and derivative d along one parameter (exact to rounding).
+struct Dual {
+  double v, d;
 };
+inline Dual operator+(Dual a, Dual b) { return {a.v + b.v, a.d + b.d}; }
+inline Dual operator-(Dual a, Dual b) { return {a.v - b.v, a.d - b.d}; }
+inline Dual operator*(Dual a, Dual b) { return {a.v * b.v, a.d * b.v + a.v * b.d}; }
+inline Dual operator/(Dual a, Dual b) { return {a.v / b.v, (a.d * b.v - a.v * b.d) / (b.v * b.v)}; }
+inline Dual operator+(Dual a, double b) { return {a.v + b, a.d}; }
+inline Dual operator+(double a, Dual b) { return {a + b.v, b.d}; }
+inline Dual operator-(Dual a, double b) { return {a.v - b, a.d}; }
+inline Dual operator-(double a, Dual b) { return {a - b.v, -b.d}; }
+inline Dual operator-(Dual a) { return {-a.v, -a.d}; }
+inline Dual operator*(double a, Dual b) { return {a * b.v, a * b.d}; }
+inline Dual operator*(Dual a, double b) { return {a.v * b, a.d * b}; }
+inline Dual operator/(double a, Dual b) { return {a / b.v, -a * b.d / (b.v * b.v)}; }
+inline Dual operator/(Dual a, double b) { return {a.v / b, a.d / b}; }
+inline Dual atan(Dual a) { return {std::atan(a.v), a.d / (1.0 + a.v * a.v)}; }
+inline double value_of(double x) { return x; }
+inline double value_of(Dual x) { return x.v; }
 
-inline Jk jastrow_ft(double Q2, double A, double C) {
-  const double ic2 = 1.0 / (C * C);
-  Jk k;
+// S is double, or Dual for derivatives with respect to A and C.
+template <class S>
+struct JkT {
+  S u, lap, w;
+};
+using Jk = JkT<double>;
+
+template <class S>
+JkT<S> jastrow_ft_t(double Q2, S A, S C) {
+  const S ic2 = 1.0 / (C * C);
+  JkT<S> k;
   k.u = kFourPi * A * (1.0 / Q2 - 1.0 / (Q2 + ic2));
   k.lap = -kFourPi * A * ic2 / (Q2 + ic2);
-  const double g = C * std::sqrt(Q2);
-  double br;
-  if (g < 1e-3) {
-    const double g2 = g * g;   // Taylor series of the bracket / g
+  const S g = C * std::sqrt(Q2);
+  S br;
+  using std::atan;
+  if (value_of(g) < 1e-3) {
+    const S g2 = g * g;   // Taylor series of the bracket / g
     br = 0.5 - kPi * g / 4.0 + 11.0 * g2 / 24.0 - 57.0 * g2 * g2 / 480.0;
   } else {
-    br = (-kPi * g * g / 4.0 - (1.0 + 0.5 * g * g) * std::atan(0.5 * g) + (1.0 + g * g) * std::atan(g)) / g;
+    br = (-kPi * g * g / 4.0 - (1.0 + 0.5 * g * g) * atan(0.5 * g) + (1.0 + g * g) * atan(g)) / g;
   }
   k.w = kFourPi * A * A / C * br;
   return k;
+}
+
+inline Jk jastrow_ft(double Q2, double A, double C) { return jastrow_ft_t<double>(Q2, A, C); }
+
+// Which kernel tables to build.
+//   OPERATOR: the operator's own kernels.
+//   GRADIENT: the scalar kernel V2a - L~ (L~ = -Q^2 u~, zero at Q = 0), i.e. 4 pi/Q^2 - (grad u)^2~ off
+//             Q = 0 and V2a(0) at Q = 0.  With the grad-u . grad terms switched off, one application with
+//             these tables gives the orbital gradient of the energy (see tc_energy_backward).
+//   TANGENT:   every quantity that depends on (A, C) moved along its exact derivative with respect to one
+//             parameter: K + h dK/dtheta (theta = A_par, A_anti, C_par, C_anti).  The energy is a
+//             polynomial of degree two in these quantities taken together, so a central difference over
+//             +-h along the tangent is its exact derivative.
+struct TableVariant {
+  enum Kind { OPERATOR = 0, GRADIENT = 1, TANGENT = 2 } kind = OPERATOR;
+  int dir = 0;
+  double h = 0;
+};
+
+// Quantity f(A_ch, C_ch) of spin channel ch (0 parallel, 1 antiparallel) for the variant: its value,
+// plus h times its derivative (forward mode) when the variant moves a parameter of this channel.
+// Tangent directions: 0 A_par, 1 A_anti, 2 C_par, 3 C_anti.
+template <class F>
+double chan_eval(const TableVariant& tv, const double* A, const double* C, int ch, F&& f) {
+  if (tv.kind != TableVariant::TANGENT || tv.dir % 2 != ch) return f(A[ch], C[ch]);
+  const Dual a{A[ch], tv.dir < 2 ? 1.0 : 0.0}, c{C[ch], tv.dir < 2 ? 0.0 : 1.0};
+  const Dual v = f(a, c);
+  return v.v + tv.h * v.d;
+}
+
+// u~, lap u~ and (grad u)^2~ of channel ch at Q^2 for the variant.
+inline Jk chan_kernels(const TableVariant& tv, const double* A, const double* C, int ch, double Q2) {
+  if (tv.kind != TableVariant::TANGENT || tv.dir % 2 != ch) return jastrow_ft(Q2, A[ch], C[ch]);
+  const Dual a{A[ch], tv.dir < 2 ? 1.0 : 0.0}, c{C[ch], tv.dir < 2 ? 0.0 : 1.0};
+  const JkT<Dual> k = jastrow_ft_t<Dual>(Q2, a, c);
+  return Jk{k.u.v + tv.h * k.u.d, k.lap.v + tv.h * k.lap.d, k.w.v + tv.h * k.w.d};
 }
 
 // ------------------------------------------------------------------ problem description (host, FP64)
@@ -167,6 +230,7 @@ struct Shared {                       // precision-independent device data
   DBuf<double> w;                     // [P]  f / N_k
   DBuf<double> dfr;                   // [nDelta][3]
   DBuf<double> out;                   // [P][npw_max] complex128 (H c)
+  DBuf<double> grad;                  // [P][npw_max] complex128 energy gradient
   DBuf<double> dhc2, dhc3;            // FP64 corrections
   DBuf<double> epart;                 // [P][4]
   DBuf<double> tkin;                  // [P]
@@ -222,6 +286,25 @@ __global__ void k_kinetic(const double* c, const double* kg, const int* npw, int
     __syncthreads();
   }
   if (threadIdx.x == 0) t[p] = red[0];
+}
+
+// Orbital gradient from an application with the GRADIENT tables and the grad-u . grad terms off:
+// grad_p = 4 w_p [(h' c_p)(G) + |k+G|^2/2 c_p(G)], w_p = f_p / N_k (both spin channels share c).
+__global__ void k_grad_finish(const double* c, const double* out, const double* kg, const int* npw, const double* w,
+                              int nb, int npw_max, int P, double* grad) {
+  const long id = long(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (id >= long(P) * npw_max) return;
+  const int p = int(id / npw_max), g = int(id - long(p) * npw_max), k = p / nb;
+  double* o = grad + 2 * id;
+  if (g >= npw[k]) {
+    o[0] = o[1] = 0.0;
+    return;
+  }
+  const double* q = kg + (long(k) * npw_max + g) * 3;
+  const double e = 0.5 * (q[0] * q[0] + q[1] * q[1] + q[2] * q[2]);
+  const double f = 4.0 * w[p];
+  o[0] = f * (out[2 * id] + e * c[2 * id]);
+  o[1] = f * (out[2 * id + 1] + e * c[2 * id + 1]);
 }
 
 // Source of the G != 0 correction of 3a2 (Eq. divcor_3a2_second, general-overlap form):
@@ -443,7 +526,7 @@ void fft3d_t(cx<R>* d, long nvol, int dir, hipStream_t s, Prof* pf = nullptr) {
 // ------------------------------------------------------------------ engine
 struct Engine {
   virtual ~Engine() = default;
-  virtual void upload_tables(const Problem& pb) = 0;
+  virtual void upload_tables(const Problem& pb, const TableVariant& tv) = 0;
   virtual void apply(hipStream_t s, Shared& sh, const Problem& pb, double* stage_ms) = 0;
   Prof* prof = nullptr;
 };
@@ -505,6 +588,7 @@ struct EngineT : Engine {
   // FP64 side of the corrections
   DBuf<cx<double>> psi64, v64, prod64;
   DBuf<double> tHu0, tHu1, focc;
+  double corrA[2] = {0, 0}, corrB[2] = {0, 0};
   int T = 1;
   int P_alloc = -1;
   int batch_alloc = -1;
@@ -519,8 +603,14 @@ struct EngineT : Engine {
     return true;
   }
 
-  // Exchange-type tables at Q = Delta + G: V2a parallel (Q = 0: 1/r dropped, L(0) - W(0)), u~ (Q = 0: 0)
-  static void fill_delta(const Problem& pb, const double* f, double scale, R* V, R* U1, R* U2) {
+  // Exchange-type tables at Q = Delta + G: V2a parallel (Q = 0: 1/r dropped, L(0) - W(0)), u~ (Q = 0: 0).
+  // GRADIENT variant: V2a - L~ (Q != 0: 4 pi/Q^2 - W; Q = 0 unchanged).
+  static void fill_delta(const Problem& pb, const TableVariant& tv, const double* f, double scale, R* V, R* U1,
+                         R* U2) {
+    const bool grad = tv.kind == TableVariant::GRADIENT;
+    const double V0 = scale * chan_eval(tv, pb.A, pb.C, 0, [](auto A, auto C) {
+                        return -kFourPi * A - 2.0 * kPi * A * A / C;
+                      });
     for (long r = 0; r < NR; ++r) {
       double Q[3], q2;
       if (!grid_q(pb, r, f, Q, q2)) {
@@ -528,31 +618,42 @@ struct EngineT : Engine {
         continue;
       }
       if (q2 < 1e-20) {
-        V[r] = R(scale * (-kFourPi * pb.A[0] - 2.0 * kPi * pb.A[0] * pb.A[0] / pb.C[0]));
+        V[r] = R(V0);
         U1[r] = U2[r] = R(0);
         continue;
       }
-      const Jk k0 = jastrow_ft(q2, pb.A[0], pb.C[0]);
-      const Jk k1 = jastrow_ft(q2, pb.A[1], pb.C[1]);
-      V[r] = R(scale * (kFourPi / q2 + k0.lap - k0.w));
+      const Jk k0 = chan_kernels(tv, pb.A, pb.C, 0, q2);
+      const Jk k1 = chan_kernels(tv, pb.A, pb.C, 1, q2);
+      V[r] = R(scale * (kFourPi / q2 + (grad ? 0.0 : k0.lap) - k0.w));
       U1[r] = R(scale * k0.u);
       U2[r] = R(scale * k1.u);
     }
   }
 
-  void upload_tables(const Problem& pb) override {
+  // Runs body(i) for i in [0, n) on the host's cores.
+  template <class F>
+  static void parallel_for(int n, F&& body) {
+    const int nt = std::max(1, std::min<int>(n, int(std::thread::hardware_concurrency())));
+    std::vector<std::thread> th;
+    for (int t = 0; t < nt; ++t)
+      th.emplace_back([&, t] {
+        for (int i = t; i < n; i += nt) body(i);
+      });
+    for (auto& x : th) x.join();
+  }
+
+  void upload_tables(const Problem& pb, const TableVariant& tv) override {
     const int nD = (2 * pb.n1 - 1) * (2 * pb.n2 - 1) * (2 * pb.n3 - 1);
     const double scale = 1.0 / (pb.omega * double(NR));
     std::vector<R> V(size_t(nD) * NR), U1(size_t(nD) * NR), U2(size_t(nD) * NR);
     std::vector<double> df(size_t(nD) * 3);
-    for (int d1 = -(pb.n1 - 1); d1 <= pb.n1 - 1; ++d1)
-      for (int d2 = -(pb.n2 - 1); d2 <= pb.n2 - 1; ++d2)
-        for (int d3 = -(pb.n3 - 1); d3 <= pb.n3 - 1; ++d3) {
-          const int di = ((d1 + pb.n1 - 1) * (2 * pb.n2 - 1) + (d2 + pb.n2 - 1)) * (2 * pb.n3 - 1) + (d3 + pb.n3 - 1);
-          const double f[3] = {double(d1) / pb.n1, double(d2) / pb.n2, double(d3) / pb.n3};
-          for (int c = 0; c < 3; ++c) df[3 * di + c] = f[c];
-          fill_delta(pb, f, scale, &V[size_t(di) * NR], &U1[size_t(di) * NR], &U2[size_t(di) * NR]);
-        }
+    const int e2 = 2 * pb.n2 - 1, e3 = 2 * pb.n3 - 1;
+    parallel_for(nD, [&](int di) {
+      const int d1 = di / (e2 * e3) - (pb.n1 - 1), d2 = (di / e3) % e2 - (pb.n2 - 1), d3 = di % e3 - (pb.n3 - 1);
+      const double f[3] = {double(d1) / pb.n1, double(d2) / pb.n2, double(d3) / pb.n3};
+      for (int c = 0; c < 3; ++c) df[3 * size_t(di) + c] = f[c];
+      fill_delta(pb, tv, f, scale, &V[size_t(di) * NR], &U1[size_t(di) * NR], &U2[size_t(di) * NR]);
+    });
     tV.alloc(V.size());
     tU1.alloc(U1.size());
     tU2.alloc(U2.size());
@@ -562,6 +663,7 @@ struct EngineT : Engine {
     TC_HIP(hipMemcpy(tU2.p, U2.data(), U2.size() * sizeof(R), hipMemcpyHostToDevice));
     TC_HIP(hipMemcpy(dfr.p, df.data(), df.size() * sizeof(double), hipMemcpyHostToDevice));
     // Hartree tables (Delta = 0, G = 0 dropped); both spin channels summed for the working precision
+    const bool grad = tv.kind == TableVariant::GRADIENT;
     std::vector<R> HV(NR), HU(NR);
     std::vector<double> hu0(NR), hu1(NR);
     for (long r = 0; r < NR; ++r) {
@@ -571,10 +673,11 @@ struct EngineT : Engine {
         hu0[r] = hu1[r] = 0;
         continue;
       }
-      const Jk k0 = jastrow_ft(q2, pb.A[0], pb.C[0]);
-      const Jk k1 = jastrow_ft(q2, pb.A[1], pb.C[1]);
+      const Jk k0 = chan_kernels(tv, pb.A, pb.C, 0, q2);
+      const Jk k1 = chan_kernels(tv, pb.A, pb.C, 1, q2);
       const double v = kFourPi / q2;
-      HV[r] = R(scale * ((v + k0.lap - k0.w) + (v + k1.lap - k1.w)));
+      const double l0 = grad ? 0.0 : k0.lap, l1 = grad ? 0.0 : k1.lap;
+      HV[r] = R(scale * ((v + l0 - k0.w) + (v + l1 - k1.w)));
       HU[r] = R(scale * (k0.u + k1.u));
       hu0[r] = scale * k0.u;
       hu1[r] = scale * k1.u;
@@ -587,6 +690,15 @@ struct EngineT : Engine {
     TC_HIP(hipMemcpy(tHU.p, HU.data(), NR * sizeof(R), hipMemcpyHostToDevice));
     TC_HIP(hipMemcpy(tHu0.p, hu0.data(), NR * sizeof(double), hipMemcpyHostToDevice));
     TC_HIP(hipMemcpy(tHu1.p, hu1.data(), NR * sizeof(double), hipMemcpyHostToDevice));
+    // correction prefactors: A (Eqs. divcor_3a2_second, 3b6_div_scf2/3) and
+    // A [4 pi A Delta_GB + u~_short(0)/N_k] with u~_short(0) = -4 pi A C^2 (Eqs. u_short, divcor_3a2_first,
+    // 3b6_div_scf1)
+    for (int ch = 0; ch < 2; ++ch) {
+      corrA[ch] = chan_eval(tv, pb.A, pb.C, ch, [](auto A, auto) { return A; });
+      corrB[ch] = chan_eval(tv, pb.A, pb.C, ch, [&](auto A, auto C) {
+        return A * (kFourPi * A * pb.delta_gb - kFourPi * A * C * C / double(pb.nk));
+      });
+    }
   }
 
   void ensure(const Problem& pb, size_t budget_bytes) {
@@ -859,7 +971,7 @@ struct EngineT : Engine {
     hipLaunchKernelGGL((k_corr_Ysrc<N>), dim3(nblk(NR)), dim3(256), 0, s, psi64.p, sh.S.p, focc.p, nk, nb,
                        1.0 / (nk * pb.omega), YG);
     fft3d_t<double, N>(nG, 2, -1, s);
-    const double a0 = 2 * kPi * pb.A[0] / nk, a1 = 2 * kPi * pb.A[1] / nk;
+    const double a0 = 2 * kPi * corrA[0] / nk, a1 = 2 * kPi * corrA[1] / nk;
     hipLaunchKernelGGL((k_corr_gfields<N>), dim3(nblk(NR)), dim3(256), 0, s, tHu0.p, tHu1.p, a0, a1, nG, F1);
     hipLaunchKernelGGL((k_corr_gfields<N>), dim3(nblk(NR)), dim3(256), 0, s, tHu0.p, tHu1.p, 2 * a0, 2 * a1, YG, F2);
     fft3d_t<double, N>(F1, 2, +1, s);
@@ -879,10 +991,8 @@ struct EngineT : Engine {
       for (int a = 0; a < nb; ++a) n0 += pb.occ[k * nb + a] / nk * S[2 * ((k * nb + a) * nb + a)] / pb.omega;
     double c1s = 0, c1a = 0;
     for (int ch = 0; ch < 2; ++ch) {
-      const double ushort = -kFourPi * pb.A[ch] * pb.C[ch] * pb.C[ch];   // Eq. u_short
-      const double br = kFourPi * pb.A[ch] * pb.delta_gb + ushort / nk;
-      c1s += 2 * kPi * pb.A[ch] * br;   // Eq. 3b6_div_scf1 (summed over the density's spin)
-      c1a += kFourPi * pb.A[ch] * br;   // Eq. divcor_3a2_first (summed over the partners' spin)
+      c1s += 2 * kPi * corrB[ch];   // Eq. 3b6_div_scf1 (summed over the density's spin)
+      c1a += kFourPi * corrB[ch];   // Eq. divcor_3a2_first (summed over the partners' spin)
     }
     double const1 = 0;
     for (int k = 0; k < nk; ++k)
@@ -998,7 +1108,7 @@ int prepare(tc_ctx* c) {
   }
   if (c->tables_dirty) {
     gb_constant(pb);
-    c->eng->upload_tables(pb);
+    c->eng->upload_tables(pb, TableVariant{});
     c->tables_dirty = false;
   }
   return TC_OK;
@@ -1030,9 +1140,8 @@ void finish_energy(tc_ctx* c) {
   c->e_total = T + E2 + E3;
 }
 
-int do_apply(tc_ctx* c, void* out_dev, double* out_host) {
-  int st = prepare(c);
-  if (st != TC_OK) return st;
+// One application with whatever tables are uploaded; energies kept for tc_energy.
+void run_apply(tc_ctx* c, void* out_dev, double* out_host) {
   Problem& pb = c->pb;
   Shared& sh = c->sh;
   const int P = pb.P();
@@ -1059,6 +1168,85 @@ int do_apply(tc_ctx* c, void* out_dev, double* out_host) {
   TC_HIP(hipStreamSynchronize(c->stream));
   finish_energy(c);
   c->have_result = true;
+}
+
+int do_apply(tc_ctx* c, void* out_dev, double* out_host) {
+  int st = prepare(c);
+  if (st != TC_OK) return st;
+  run_apply(c, out_dev, out_host);
+  return TC_OK;
+}
+
+constexpr uint64_t kTermsB = TC_T_2BH1 | TC_T_2BH2 | TC_T_2BX1 | TC_T_2BX2;
+constexpr uint64_t kTerms3 = TC_T_3A1 | TC_T_3A2 | TC_T_3A3 | TC_T_3A4 | TC_T_3B1 | TC_T_3B2 | TC_T_3B3 | TC_T_3B4 |
+                             TC_T_3B5 | TC_T_3B6;
+
+// Gradient of the energy of the loaded orbitals.
+//  * Orbitals: the two-body V2a terms (with C2ax) and the whole three-body operator (with its
+//    corrections) are the exact first variations of their energies and are Hermitian in the discrete
+//    form, so their gradient is 4 w_p h c_p.  The grad-u . grad terms are not Hermitian: their
+//    gradient is minus the pair operator with kernel L~ = -Q^2 u~ (zero at Q = 0).  Both are obtained
+//    by one application with V2a replaced by V2a - L~ and the grad-u . grad terms off.
+//  * A and C: central differences along exact tangent tables (TableVariant::TANGENT), exact because
+//    the energy is quadratic in the tables and correction prefactors taken together.
+int do_backward(tc_ctx* c, void* grad_dev, double* grad_host, double* dA, double* dC) {
+  Problem& pb = c->pb;
+  const uint64_t m = pb.mask;
+  if ((m & kTermsB) != 0 && (m & kTermsB) != kTermsB)
+    return fail(c, TC_ERR_UNSUPPORTED, "the gradient needs 2bh1, 2bh2, 2bx1 and 2bx2 selected together");
+  if ((m & kTerms3) != 0 && (m & kTerms3) != kTerms3)
+    return fail(c, TC_ERR_UNSUPPORTED, "the gradient needs all three-body terms or none");
+  if ((m & kTermsB) != 0 && (m & (TC_T_2AH | TC_T_2AX)) != (TC_T_2AH | TC_T_2AX))
+    return fail(c, TC_ERR_UNSUPPORTED, "the gradient of the grad-u . grad terms needs 2ah and 2ax selected");
+  int st = prepare(c);
+  if (st != TC_OK) return st;
+  struct Keep {
+    tc_ctx* c;
+    uint64_t mask;
+    double e, parts[TC_E_NPARTS], stage[6], total;
+    bool had;
+    ~Keep() {
+      c->pb.mask = mask;
+      c->tables_dirty = true;   // the next application rebuilds the operator's tables
+      c->e_total = e;
+      std::memcpy(c->e_parts, parts, sizeof(parts));
+      std::memcpy(c->stage_ms, stage, sizeof(stage));
+      c->total_ms = total;
+      c->have_result = had;
+    }
+  } keep{c, m, c->e_total, {}, {}, c->total_ms, c->have_result};
+  std::memcpy(keep.parts, c->e_parts, sizeof(keep.parts));
+  std::memcpy(keep.stage, c->stage_ms, sizeof(keep.stage));
+  Shared& sh = c->sh;
+  const int P = pb.P();
+  if (grad_dev || grad_host) {
+    pb.mask = m & ~kTermsB;
+    c->tables_dirty = true;
+    c->eng->upload_tables(pb, TableVariant{TableVariant::GRADIENT, 0, 0.0});
+    run_apply(c, nullptr, nullptr);
+    sh.grad.alloc(size_t(2) * P * pb.npw_max);
+    hipLaunchKernelGGL(k_grad_finish, dim3(nblk(long(P) * pb.npw_max)), dim3(256), 0, c->stream, sh.coef.p, sh.out.p,
+                       sh.kg.p, sh.npw.p, sh.w.p, pb.nb, pb.npw_max, P, sh.grad.p);
+    const size_t bytes = size_t(2) * P * pb.npw_max * sizeof(double);
+    if (grad_dev) TC_HIP(hipMemcpyAsync(grad_dev, sh.grad.p, bytes, hipMemcpyDeviceToDevice, c->stream));
+    if (grad_host) TC_HIP(hipMemcpyAsync(grad_host, sh.grad.p, bytes, hipMemcpyDeviceToHost, c->stream));
+    TC_HIP(hipStreamSynchronize(c->stream));
+    pb.mask = m;
+  }
+  for (int dir = 0; dir < 4; ++dir) {
+    double* dst = dir < 2 ? (dA ? dA + dir : nullptr) : (dC ? dC + dir - 2 : nullptr);
+    if (!dst) continue;
+    const double th = dir < 2 ? pb.A[dir] : pb.C[dir - 2];
+    const double h = std::max(std::fabs(th), 0.1);
+    double e[2];
+    for (int sgn = 0; sgn < 2; ++sgn) {
+      c->tables_dirty = true;
+      c->eng->upload_tables(pb, TableVariant{TableVariant::TANGENT, dir, sgn ? -h : h});
+      run_apply(c, nullptr, nullptr);
+      e[sgn] = c->e_total;
+    }
+    *dst = (e[0] - e[1]) / (2.0 * h);
+  }
   return TC_OK;
 }
 
@@ -1325,10 +1513,15 @@ int tc_energy(tc_ctx* c, double* e_total, double* e_parts) {
 
 int tc_energy_backward(tc_ctx* c, double* grad, double dA[2], double dC[2]) {
   return guard(c, [&]() -> int {
-    (void)grad;
-    (void)dA;
-    (void)dC;
-    return fail(c, TC_ERR_UNSUPPORTED, "gradient not built yet");
+    if (!grad && !dA && !dC) return fail(c, TC_ERR_ARG, "nothing requested");
+    return do_backward(c, nullptr, grad, dA, dC);
+  });
+}
+
+int tc_energy_backward_dev(tc_ctx* c, void* grad_dev, double dA[2], double dC[2]) {
+  return guard(c, [&]() -> int {
+    if (!grad_dev && !dA && !dC) return fail(c, TC_ERR_ARG, "nothing requested");
+    return do_backward(c, grad_dev, nullptr, dA, dC);
   });
 }
 

@@ -1,0 +1,142 @@
+"""Energy gradient (orbital coefficients, Jastrow A and C) of the HIP path, through the C ABI.
+
+Small cases: against the oracle's gradient (reverse-mode differentiation of the
+oracle's own discrete energy, itself pinned to finite differences on the CPU).
+Full bench-workload shape (fcc 4x4x4, 256 orbitals, 24^3): against central
+differences of the library's FP64 energy along random directions.
+"""
+import numpy as np
+import pytest
+
+import tcinputs as T
+from oracle import grad as OG
+
+pytestmark = pytest.mark.gpu
+
+tc = pytest.importorskip("paper_2302_07420_amd")
+
+CASES = {
+    "fcc_k211_g8_partial": lambda: T.tiny_fcc(kmesh=(2, 1, 1), grid=8, ecut=2.0, nb=2, a=6.0, occ=[1.0, 0.6]),
+    "fcc_k221_g12": lambda: T.tiny_fcc(kmesh=(2, 2, 1), grid=12, ecut=2.0, nb=2, a=6.0, occ=[1.0, 0.8]),
+    "heg14_g16": lambda: T.workload("heg14_g16"),
+}
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+@pytest.fixture(scope="module", params=list(CASES))
+def case(request):
+    w = CASES[request.param]()
+    return request.param, w, OG.energy_and_grad(w)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_gradient_matches_oracle(case, prec):
+    name, w, (E, gc, gA, gC) = case
+    _say(f"[gpu] backward {name} {prec} vs oracle autograd")
+    op = tc.from_workload(w, precision=tc.TC_PREC_FP64 if prec == "fp64" else tc.TC_PREC_FP32)
+    Eg, _ = op.energy()
+    g, dA, dC = op.backward()
+    E2, _ = op.energy()                  # energies of the last application survive the backward
+    op.close()
+    tol = 1e-10 if prec == "fp64" else 2e-6
+    scale = max(np.abs(x).max() for x in gc)
+    err = max(np.abs(a - b).max() for a, b in zip(g, gc)) / scale
+    pscale = max(np.abs(gA).max(), np.abs(gC).max())
+    perr = max(np.abs(dA - gA).max(), np.abs(dC - gC).max()) / pscale
+    _say(f"    grad rel err {err:.3e}; dA {dA} vs {gA}; dC {dC} vs {gC}; rel {perr:.3e}")
+    assert E2 == Eg
+    assert err < tol
+    assert perr < (1e-10 if prec == "fp64" else 1e-6)
+
+
+def test_gradient_device_buffer_equals_host():
+    import torch
+
+    w = CASES["fcc_k221_g12"]()
+    _say("[gpu] backward_dev equals backward")
+    op = tc.from_workload(w, precision=tc.TC_PREC_FP64)
+    g, dA, dC = op.backward()
+    buf = torch.zeros((w.nk, w.right[0].shape[0], op.npw_max), dtype=torch.complex128, device="cuda")
+    dA2, dC2 = op.backward_dev(buf.data_ptr())
+    op.close()
+    got = buf.cpu().numpy()
+    for k in range(w.nk):
+        np.testing.assert_array_equal(got[k, :, : g[k].shape[1]], g[k])
+    np.testing.assert_array_equal(dA, dA2)
+    np.testing.assert_array_equal(dC, dC2)
+
+
+def test_bench_workload_gradient_directional_fp64():
+    w = T.workload("fcc_si_k444_g24")
+    _say("[gpu] backward fcc_si_k444_g24 fp64: directional derivatives vs central differences")
+    op = tc.from_workload(w, precision=tc.TC_PREC_FP64)
+    g, dA, dC = op.backward()
+    rng = np.random.default_rng(7)
+    h = 1e-4
+    gmax = max(np.abs(x).max() for x in g)
+    for trial in range(2):
+        # directions on the scale of the coefficients (~1/sqrt(npw)), with a component along the
+        # gradient so that the derivative is well above the rounding of the energy differences
+        d = [0.05 * (gk / gmax + 0.5 * (rng.standard_normal(c.shape) + 1j * rng.standard_normal(c.shape)))
+             for gk, c in zip(g, w.right)]
+        e = []
+        for sgn in (1, -1):
+            for ik in range(w.nk):
+                op.load_orbitals(ik, w.right[ik] + sgn * h * d[ik], w.occ[ik])
+            e.append(op.energy()[0])
+        fd = (e[0] - e[1]) / (2 * h)
+        an = sum(np.sum((np.conj(gk) * dk).real) for gk, dk in zip(g, d))
+        _say(f"    direction {trial}: analytic {an!r} central difference {fd!r}")
+        assert an == pytest.approx(fd, rel=1e-6)
+    for ik in range(w.nk):
+        op.load_orbitals(ik, w.right[ik], w.occ[ik])
+    for which in ("A", "C"):
+        for s in (0, 1):
+            A, C = np.array(w.A, float), np.array(w.C, float)
+            e = []
+            for sgn in (1, -1):
+                A2, C2 = A.copy(), C.copy()
+                (A2 if which == "A" else C2)[s] += sgn * 1e-4
+                op.set_jastrow(A2, C2)
+                e.append(op.energy()[0])
+            fd = (e[0] - e[1]) / 2e-4
+            an = (dA if which == "A" else dC)[s]
+            _say(f"    d{which}[{s}]: analytic {an!r} central difference {fd!r}")
+            assert an == pytest.approx(fd, rel=1e-6, abs=1e-9)
+    op.close()
+
+
+def test_bench_workload_gradient_fp32_vs_fp64():
+    w = T.workload("fcc_si_k444_g24")
+    _say("[gpu] backward fcc_si_k444_g24: fp32 vs fp64")
+    res = {}
+    for name, prec in (("fp64", tc.TC_PREC_FP64), ("fp32", tc.TC_PREC_FP32)):
+        op = tc.from_workload(w, precision=prec)
+        res[name] = op.backward()
+        op.close()
+    g64, dA64, dC64 = res["fp64"]
+    g32, dA32, dC32 = res["fp32"]
+    scale = max(np.abs(x).max() for x in g64)
+    err = max(np.abs(a - b).max() for a, b in zip(g32, g64)) / scale
+    _say(f"    grad rel diff {err:.3e}; dA {dA32} vs {dA64}; dC {dC32} vs {dC64}")
+    assert err < 2e-6
+    assert np.abs(dA32 - dA64).max() < 1e-6 * np.abs(dA64).max()
+    assert np.abs(dC32 - dC64).max() < 1e-6 * np.abs(dC64).max()
+
+
+def test_backward_error_paths():
+    w = CASES["fcc_k211_g8_partial"]()
+    _say("[gpu] backward error paths")
+    op = tc.from_workload(w, precision=tc.TC_PREC_FP64, terms=tc.TERM_BITS["3a2"])
+    with pytest.raises(tc.TCError, match="status -5"):
+        op.backward()
+    op.set_options(tc.TC_PREC_FP64, w.alpha, True, tc.TERM_BITS["2bh1"] | tc.TERM_BITS["2bh2"] |
+                   tc.TERM_BITS["2bx1"] | tc.TERM_BITS["2bx2"])
+    with pytest.raises(tc.TCError, match="status -5"):
+        op.backward()
+    with pytest.raises(tc.TCError, match="status -1"):
+        op.backward(want_grad=False, want_params=False)
+    op.close()
