@@ -190,10 +190,10 @@ enum {
   TC_K_FFT_XY_INV = 2,  /* k_fft_xy<R,N,+1>: inverse xy-plane transforms                */
   TC_K_FFT_Z_FWD = 3,   /* k_fft_z<R,N,-1>                                               */
   TC_K_FFT_Z_INV = 4,   /* k_fft_z<R,N,+1>                                               */
-  TC_K_XY_PAIR_OCC = 5, /* k_xy_pair<R,N,true>: occupied-occupied pair densities, fwd xy */
-  TC_K_XY_PAIR_TGT = 6, /* k_xy_pair<R,N,false>: target-partner pair densities, fwd xy  */
+  TC_K_XY_PAIR_OCC = 5, /* k_pair_xy<R,N,true>: occupied-occupied pair densities, fwd xy */
+  TC_K_XY_PAIR_TGT = 6, /* k_pair_xy<R,N,false>: target-partner pair densities, fwd xy  */
   TC_K_SUM_PARTS = 7,   /* k_sum_parts: fixed-order sums of the partner-chunk partials  */
-  TC_K_XY_PASSB = 8,    /* k_xy_passB: pass-B sources, fwd xy                           */
+  TC_K_XY_PASSB = 8,    /* k_passB_xy: pass-B sources, fwd xy                           */
   TC_K_ZCONV_OCC = 9,   /* k_zconv<R,N,OP_O>                                            */
   TC_K_ZCONV_A1 = 10,   /* k_zconv<R,N,OP_A1>                                           */
   TC_K_ZCONV_A2 = 11,   /* k_zconv<R,N,OP_A2>                                           */

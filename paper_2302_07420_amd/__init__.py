@@ -27,7 +27,7 @@ TERM_ALL = (1 << 17) - 1
 E_PARTS = ("kinetic", "two_body", "three_body", "corrections")
 # kernel index -> symbol stem (working precision R, grid length N), see TC_K_* in include/tcmi.h
 KERNELS = ("k_scatter", "k_fft_xy<R,N,-1>", "k_fft_xy<R,N,1>", "k_fft_z<R,N,-1>", "k_fft_z<R,N,1>",
-           "k_xy_pair<R,N,true>", "k_xy_pair<R,N,false>", "k_sum_parts<R,N>", "k_xy_passB<R,N>",
+           "k_pair_xy<R,N,true>", "k_pair_xy<R,N,false>", "k_sum_parts<R,N>", "k_passB_xy<R,N>",
            "k_zconv<R,N,OP_O>", "k_zconv<R,N,OP_A1>", "k_zconv<R,N,OP_A2>", "k_zconv<R,N,OP_B>",
            "k_fused_O<R,N>", "k_fused_A<R,N>", "k_fused_Y<R,N>", "other", "fp64_corrections")
 STAGES = ("g_to_r", "hartree", "occ_occ", "pass_a", "pass_b", "out_and_corrections")

@@ -564,6 +564,7 @@ template <typename R, int N>
 struct EngineT : Engine {
   static constexpr long NR = long(N) * N * N;
   static constexpr int PB = XY<R, N>::PB;
+  static constexpr int NTH = Fz<R, N>::NTH;
   // working-precision fields
   DBuf<cx<R>> psi;     // [P][NR]
   DBuf<cx<R>> D;       // [3][P][NR]
@@ -572,8 +573,8 @@ struct EngineT : Engine {
   DBuf<cx<R>> wk;      // [9][NR]  scratch volumes
   DBuf<cx<R>> H3a4;    // [P][3][NR]
   DBuf<R> h5;          // [P][NR]
-  DBuf<cx<R>> bufA;    // [T*P][6][NR]
-  DBuf<cx<R>> bufB;    // [T*P][7][NR]
+  DBuf<cx<R>> bufA;    // [T*P][4][NR]  pair densities, 3b6 and pass-B sources
+  DBuf<cx<R>> bufB;    // [T*P][5][NR]  z-stage outputs
   DBuf<cx<R>> h4, Z;   // [T][3][NR]
   DBuf<cx<R>> g;       // [T][NR]
   DBuf<cx<double>> acc;     // [4][T][NR]  FP64 accumulation of the operator output, per energy slot
@@ -711,11 +712,11 @@ struct EngineT : Engine {
     wk.alloc(9 * NR);
     H3a4.alloc(size_t(3) * P * NR);
     h5.alloc(size_t(P) * NR);
-    const size_t per_t = size_t(P) * 13 * NR * sizeof(cx<R>);
+    const size_t per_t = size_t(P) * 9 * NR * sizeof(cx<R>);
     T = int(std::max<size_t>(1, std::min<size_t>(size_t(P), budget_bytes / per_t)));
     if (pb.batch > 0) T = std::min(pb.batch, P);
-    bufA.alloc(size_t(T) * P * 6 * NR);
-    bufB.alloc(size_t(T) * P * 7 * NR);
+    bufA.alloc(size_t(T) * P * 4 * NR);
+    bufB.alloc(size_t(T) * P * 5 * NR);
     h4.alloc(size_t(3) * T * NR);
     Z.alloc(size_t(3) * T * NR);
     g.alloc(size_t(T) * NR);
@@ -806,16 +807,16 @@ struct EngineT : Engine {
         const long npair = long(nt) * P;
         const FusedArgs fa{P, nt, a0, S, chunk};
         K(TC_K_XY_PAIR_OCC, fb * (npair + nt + P), [&] {
-          hipLaunchKernelGGL((k_xy_pair<R, N, true>), dim3(nblk(npair * N, PB)), dim3(PB * N), 0, s, psi.p, psi.p,
-                             bufA.p, a0, P, npair * N);
+          hipLaunchKernelGGL((k_pair_xy<R, N, true>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, psi.p, fa,
+                             bufA.p);
         });
-        K(TC_K_ZCONV_OCC, fb * 7.0 * npair + tabB, [&] {
+        K(TC_K_ZCONV_OCC, fb * 5.0 * npair + tabB, [&] {
           hipLaunchKernelGGL((k_zconv<R, N, OP_O>), dim3(nblk(npair * N * N)), dim3(256), 0, s, bufA.p, bufB.p,
-                             npair, a0, mi, rc, tb, 0);
+                             npair, a0, mi, tb, 0);
         });
-        K(TC_K_FUSED_O, fb * (6.0 * npair + P) + 4.0 * fb * nt * S, [&] {
-          hipLaunchKernelGGL((k_fused_O<R, N>), dim3(unsigned(nt) * N * S), dim3(Fz<R, N>::NTH), 0, s, bufB.p, psi.p,
-                             sh.w.p, fa, h5part.p, H3part.p);
+        K(TC_K_FUSED_O, fb * (4.0 * npair + P) + 3.5 * fb * nt * S, [&] {
+          hipLaunchKernelGGL((k_fused_O<R, N>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, bufB.p, psi.p, sh.w.p,
+                             fa, mi, rc, dfr.p, h5part.p, H3part.p);
         });
         K(TC_K_SUM_PARTS, 4.0 * fb * nt * (S + 1), [&] {
           hipLaunchKernelGGL((k_sum_parts<R, N>), dim3(nblk(long(nt) * NR)), dim3(256), 0, s, 0, S, nt, a0, 0,
@@ -852,31 +853,32 @@ struct EngineT : Engine {
       TC_HIP(hipEventRecord(be[0], s));
       const double part = fb * nt * S;   // one working-precision field per (chunk, target)
       if (need_A) {
-        K(TC_K_XY_PAIR_TGT, fb * (npair + nt + P), [&] {
-          hipLaunchKernelGGL((k_xy_pair<R, N, false>), dim3(nblk(npair * N, PB)), dim3(PB * N), 0, s, psi.p, psi.p,
-                             bufA.p, t0, P, npair * N);
-        });
-        K(TC_K_ZCONV_A1, fb * 8.0 * npair + tabB, [&] {
-          hipLaunchKernelGGL((k_zconv<R, N, OP_A1>), dim3(nblk(npair * N * N)), dim3(256), 0, s, bufA.p, bufB.p,
-                             npair, t0, mi, rc, tb, 1);
-        });
         const FusedArgs fa{P, nt, t0, S, chunk};
-        K(TC_K_FUSED_A, fb * ((m.m3b6 ? 13.0 : 7.0) * npair + 8.0 * P + nt) + 6.0 * part, [&] {
-          hipLaunchKernelGGL((k_fused_A<R, N>), dim3(unsigned(nt) * N * S), dim3(Fz<R, N>::NTH), 0, s, bufB.p, psi.p,
-                             D.p, H3a4.p, nJ.p, sh.w.p, fa, m, int(m.m3b6 != 0), bufA.p, gpart.p, h4part.p);
+        K(TC_K_XY_PAIR_TGT, fb * (npair + nt + P), [&] {
+          hipLaunchKernelGGL((k_pair_xy<R, N, false>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, psi.p, fa,
+                             bufA.p);
+        });
+        K(TC_K_ZCONV_A1, fb * 6.0 * npair + tabB, [&] {
+          hipLaunchKernelGGL((k_zconv<R, N, OP_A1>), dim3(nblk(npair * N * N)), dim3(256), 0, s, bufA.p, bufB.p,
+                             npair, t0, mi, tb, 1);
+        });
+        K(TC_K_FUSED_A, fb * ((m.m3b6 ? 9.0 : 5.0) * npair + 8.0 * P + nt) + 6.0 * part, [&] {
+          hipLaunchKernelGGL((k_fused_A<R, N>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, bufB.p, psi.p, D.p,
+                             H3a4.p, nJ.p, sh.w.p, fa, m, int(m.m3b6 != 0), mi, rc, dfr.p, bufA.p, gpart.p,
+                             h4part.p);
         });
         K(TC_K_SUM_PARTS, 6.0 * part + 6.0 * fd * nt + 3.0 * fb * nt, [&] {
           hipLaunchKernelGGL((k_sum_parts<R, N>), dim3(nblk(long(nt) * NR)), dim3(256), 0, s, 1, S, nt, t0, 0, nullptr,
                              nullptr, gpart.p, h4part.p, nullptr, nullptr, acc.p, h4.p);
         });
         if (m.m3b6) {
-          K(TC_K_ZCONV_A2, fb * 7.0 * npair + tabB, [&] {
+          K(TC_K_ZCONV_A2, fb * 5.0 * npair + tabB, [&] {
             hipLaunchKernelGGL((k_zconv<R, N, OP_A2>), dim3(nblk(npair * N * N)), dim3(256), 0, s, bufA.p, bufB.p,
-                               npair, t0, mi, rc, tb, 1);
+                               npair, t0, mi, tb, 1);
           });
           K(TC_K_FUSED_Y, fb * (npair + P) + part, [&] {
-            hipLaunchKernelGGL((k_fused_Y<R, N>), dim3(unsigned(nt) * N * S), dim3(Fz<R, N>::NTH), 0, s, bufB.p,
-                               psi.p, sh.w.p, fa, 1.0, gpart.p);
+            hipLaunchKernelGGL((k_fused_Y<R, N>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, bufB.p, psi.p,
+                               sh.w.p, fa, 1.0, gpart.p);
           });
           K(TC_K_SUM_PARTS, part + 2.0 * fd * nt, [&] {
             hipLaunchKernelGGL((k_sum_parts<R, N>), dim3(nblk(long(nt) * NR)), dim3(256), 0, s, 2, S, nt, t0, 2,
@@ -886,23 +888,22 @@ struct EngineT : Engine {
       }
       TC_HIP(hipEventRecord(be[1], s));
       if (need_B) {
-        const long np = npair * 3 * N;
+        const FusedArgs fy{P, nt, t0, S, chunk};
         K(TC_K_OTHER, fb * 13.0 * nt, [&] {
           hipLaunchKernelGGL((k_passB_Z<R, N>), dim3(nblk(long(nt) * NR)), dim3(256), 0, s, psi.p, D.p, loc.p + NR,
                              h4.p, t0, nt, P, m, Z.p);
         });
-        K(TC_K_XY_PASSB, fb * (3.0 * npair + 4.0 * P + 4.0 * nt), [&] {
-          hipLaunchKernelGGL((k_xy_passB<R, N>), dim3(nblk(np, PB)), dim3(PB * N), 0, s, psi.p, Z.p, H3a4.p, bufA.p,
-                             t0, P, R(m.m3b5), np);
+        K(TC_K_XY_PASSB, fb * (2.0 * npair + 4.0 * P + 4.0 * nt), [&] {
+          hipLaunchKernelGGL((k_passB_xy<R, N>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, psi.p, Z.p, H3a4.p, fy,
+                             mi, rc, dfr.p, R(m.m3b5), bufA.p);
         });
-        K(TC_K_ZCONV_B, fb * 4.0 * npair + tabB, [&] {
+        K(TC_K_ZCONV_B, fb * 3.0 * npair + tabB, [&] {
           hipLaunchKernelGGL((k_zconv<R, N, OP_B>), dim3(nblk(npair * N * N)), dim3(256), 0, s, bufA.p, bufB.p,
-                             npair, t0, mi, rc, tb, 1);
+                             npair, t0, mi, tb, 1);
         });
-        const FusedArgs fy{P, nt, t0, S, chunk};
         K(TC_K_FUSED_Y, fb * (npair + P) + part, [&] {
-          hipLaunchKernelGGL((k_fused_Y<R, N>), dim3(unsigned(nt) * N * S), dim3(Fz<R, N>::NTH), 0, s, bufB.p, psi.p,
-                             sh.w.p, fy, 1.0, gpart.p);
+          hipLaunchKernelGGL((k_fused_Y<R, N>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, bufB.p, psi.p, sh.w.p,
+                             fy, 1.0, gpart.p);
         });
         K(TC_K_SUM_PARTS, part + 2.0 * fd * nt, [&] {
           hipLaunchKernelGGL((k_sum_parts<R, N>), dim3(nblk(long(nt) * NR)), dim3(256), 0, s, 2, S, nt, t0, 3, nullptr,

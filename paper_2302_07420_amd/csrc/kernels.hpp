@@ -231,210 +231,93 @@ __global__ void k_mul_vec_scalar(const cx<R>* v, const cx<R>* s, cx<R>* out) {
 }
 
 // ---------------------------------------------------------------- pair passes
-// Forward xy transform of pair densities rho = conj(X[ix]) Y[iy].
-// TFIRST: ix = t0 + t, iy = q (occupied-occupied pass, rho_ab = conj(chi_a) psi_b);
-// else   ix = q, iy = t0 + t  (target passes, rho_qj = conj(chi_q) psi_j).
-template <typename R, int N, bool TFIRST>
-struct IOPair {
-  const cx<R>* X;
-  const cx<R>* Y;
-  cx<R>* out;
-  int t0, P;
-  __device__ cx<R> load(long pl, int y, int x) const {
-    constexpr long NR = long(N) * N * N;
-    const long pair = pl / N;
-    const int z = int(pl - pair * N);
-    const int t = int(pair / P), q = int(pair - long(t) * P);
-    const long ix = TFIRST ? t0 + t : q, iy = TFIRST ? q : t0 + t;
-    const long o = long(z) * N * N + y * N + x;
-    return cmulc(X[ix * NR + o], Y[iy * NR + o]);
-  }
-  __device__ void store(long pl, int y, int x, cx<R> v) const { out[pl * N * N + y * N + x] = v; }
-};
+// Lattice components of the vector kernel.  With kappa_d = m_d + delta_d (grid frequency plus the
+// pair's shift Delta, both in units of the reciprocal rows b_d), Q_c = sum_d kappa_d B_dc.  The
+// Cartesian fields i Q_c u~ rho~ are therefore sum_d B_dc Y_d with Y_d = i kappa_d u~ rho~.  Along a
+// z column kappa_1 and kappa_2 are constant, so the z stage needs two fields per spin channel,
+// W0 = u~ rho~ and W3 = i kappa_3 u~ rho~, and the xy stage forms Y_1 = i kappa_1 W0,
+// Y_2 = i kappa_2 W0, Y_3 = W3 before its inverse transform.  Forward contractions
+// sum_c Q_c S~_c = sum_d kappa_d T~_d (T_d = sum_c B_dc S_c) are split the same way: the xy stage
+// emits P = kappa_1 T~_1 + kappa_2 T~_2 and R = T~_3 and the z stage adds kappa_3 R~ to P~.
+// Every plane kernel below uses one work-group per (target, z-plane, chunk of partners).
 
-template <typename R, int N, bool TFIRST>
-__global__ void __launch_bounds__(256) k_xy_pair(const cx<R>* X, const cx<R>* Y, cx<R>* out, int t0, int P,
-                                                 long nplanes) {
-  IOPair<R, N, TFIRST> io{X, Y, out, t0, P};
-  xy_block<R, N, -1>(io, nplanes);
-}
-
-// Pass-B sources: Y_c = conj(psi_q) Z_tc + m3b5 * H3b_qc * psi_j, H3b = conj(H3a4) (TC mode);
-// Z holds D_j - h1 psi_j + h4_j (masked) per target.
-template <typename R, int N>
-struct IOPassB {
-  const cx<R>* psi;
-  const cx<R>* Z;
-  const cx<R>* H3a4;
-  cx<R>* out;
-  int t0, P;
-  R m3b5;
-  __device__ cx<R> load(long pl, int y, int x) const {
-    constexpr long NR = long(N) * N * N;
-    const long f = pl / N;              // pair*3 + c
-    const int z = int(pl - f * N);
-    const long pair = f / 3;
-    const int c = int(f - pair * 3);
-    const int t = int(pair / P), q = int(pair - long(t) * P);
-    const long o = long(z) * N * N + y * N + x;
-    const cx<R> pq = psi[long(q) * NR + o];
-    cx<R> v = cmulc(pq, Z[(long(t) * 3 + c) * NR + o]);
-    if (m3b5 != R(0)) v = v + m3b5 * cmulc(H3a4[(long(q) * 3 + c) * NR + o], psi[long(t0 + t) * NR + o]);
-    return v;
-  }
-  __device__ void store(long pl, int y, int x, cx<R> v) const { out[pl * N * N + y * N + x] = v; }
-};
-
-template <typename R, int N>
-__global__ void __launch_bounds__(256) k_xy_passB(const cx<R>* psi, const cx<R>* Z, const cx<R>* H3a4, cx<R>* out,
-                                                  int t0, int P, R m3b5, long nplanes) {
-  IOPassB<R, N> io{psi, Z, H3a4, out, t0, P, m3b5};
-  xy_block<R, N, -1>(io, nplanes);
-}
-
-// z stage of a pair convolution: forward z transform of the inputs, kernel multiply
-// at Q = Delta + G for the pair's Delta, inverse z transform of each output.
-//   OP_A1: 1 -> 7   [V2a_par rho, iQ u_par rho (3), iQ u_anti rho (3)]
-//   OP_O : 1 -> 6   [iQ u_par rho (3), iQ u_anti rho (3)]
-//   OP_A2: 6 -> 1   sum_c -iQ_c (u_par S_par,c + u_anti S_anti,c)
-//   OP_B : 3 -> 1   sum_c  iQ_c u_par Y_c
 enum { OP_A1 = 0, OP_O = 1, OP_A2 = 2, OP_B = 3 };
 
-template <int OP>
-struct OpShape;
-template <> struct OpShape<OP_A1> { static constexpr int nin = 1, nout = 7; };
-template <> struct OpShape<OP_O> { static constexpr int nin = 1, nout = 6; };
-template <> struct OpShape<OP_A2> { static constexpr int nin = 6, nout = 1; };
-template <> struct OpShape<OP_B> { static constexpr int nin = 3, nout = 1; };
-
 struct Tables {
-  const void* V;    // V2a (parallel), exchange conventions, [nDelta][N^3]
-  const void* U1;   // u~ parallel
-  const void* U2;   // u~ antiparallel
+  const void* V;      // V2a (parallel), exchange conventions, [nDelta][N^3]
+  const void* U1;     // u~ parallel
+  const void* U2;     // u~ antiparallel
   const double* dfr;  // [nDelta][3] fractions of Delta
 };
 
-template <typename R, int N, int OP>
-__global__ void __launch_bounds__(256) k_zconv(const cx<R>* in, cx<R>* out, long npairs, int t0, MeshInfo mi,
-                                               Recip rc, Tables tb, int sign_target_minus_partner) {
-  constexpr int NN = N * N;
-  constexpr long NR = long(N) * N * N;
-  constexpr int NIN = OpShape<OP>::nin, NOUT = OpShape<OP>::nout;
-  const long col = long(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (col >= npairs * NN) return;
-  const long pair = col / NN;
-  const int xy = int(col - pair * NN);
-  const int x = xy % N, y = xy / N;
-  const int t = int(pair / mi.P), q = int(pair - long(t) * mi.P);
-  const int kt = (t0 + t) / mi.nb, kq = q / mi.nb;
-  const int di = sign_target_minus_partner ? kindex_delta(mi, kt, kq) : kindex_delta(mi, kq, kt);
-  const R* tV = reinterpret_cast<const R*>(tb.V) + long(di) * NR;
-  const R* tU1 = reinterpret_cast<const R*>(tb.U1) + long(di) * NR;
-  const R* tU2 = reinterpret_cast<const R*>(tb.U2) + long(di) * NR;
-  const double* dfr = tb.dfr + 3 * di;
-
-  cx<R> acc[N];
-  if constexpr (NIN == 1) {
-    const cx<R>* b = in + pair * NR + xy;
-#pragma unroll
-    for (int z = 0; z < N; ++z) acc[z] = b[z * NN];
-    fft_line<R, N, -1>(acc);
-  } else {
-#pragma unroll
-    for (int z = 0; z < N; ++z) acc[z] = mk<R>(R(0), R(0));
-#pragma unroll 1
-    for (int c = 0; c < NIN; ++c) {
-      cx<R> v[N];
-      const cx<R>* b = in + (pair * NIN + c) * NR + xy;
-#pragma unroll
-      for (int z = 0; z < N; ++z) v[z] = b[z * NN];
-      fft_line<R, N, -1>(v);
-#pragma unroll
-      for (int z = 0; z < N; ++z) {
-        R Q[3];
-        qvec<R, N>(rc, dfr, x, y, z, Q);
-        const long o = long(z) * NN + xy;
-        if constexpr (OP == OP_A2) {
-          const int s = c / 3, cc = c - 3 * (c / 3);
-          const R u = s == 0 ? tU1[o] : tU2[o];
-          acc[z] = acc[z] + mul_i((-Q[cc] * u) * v[z]);
-        } else {  // OP_B
-          acc[z] = acc[z] + mul_i((Q[c] * tU1[o]) * v[z]);
-        }
-      }
-    }
-  }
-  if constexpr (NOUT == 1) {
-    fft_line<R, N, 1>(acc);
-    cx<R>* b = out + pair * NR + xy;
-#pragma unroll
-    for (int z = 0; z < N; ++z) b[z * NN] = acc[z];
-  } else {
-#pragma unroll 1
-    for (int o = 0; o < NOUT; ++o) {
-      cx<R> v[N];
-#pragma unroll
-      for (int z = 0; z < N; ++z) {
-        const long oo = long(z) * NN + xy;
-        if constexpr (OP == OP_A1) {
-          if (o == 0) {
-            v[z] = tV[oo] * acc[z];
-          } else {
-            R Q[3];
-            qvec<R, N>(rc, dfr, x, y, z, Q);
-            const int s = (o - 1) / 3, cc = (o - 1) - 3 * ((o - 1) / 3);
-            const R u = s == 0 ? tU1[oo] : tU2[oo];
-            v[z] = mul_i((Q[cc] * u) * acc[z]);
-          }
-        } else {  // OP_O
-          R Q[3];
-          qvec<R, N>(rc, dfr, x, y, z, Q);
-          const int s = o / 3, cc = o - 3 * (o / 3);
-          const R u = s == 0 ? tU1[oo] : tU2[oo];
-          v[z] = mul_i((Q[cc] * u) * acc[z]);
-        }
-      }
-      fft_line<R, N, 1>(v);
-      cx<R>* b = out + (pair * NOUT + o) * NR + xy;
-#pragma unroll
-      for (int z = 0; z < N; ++z) b[z * NN] = v[z];
-    }
-  }
-}
-
-// ---------------------------------------------------------------- masks
 struct Masks {
   double m2ah, m2bh1, m2bh2, m2ax, m2bx1, m2bx2, m3a1, m3a2, m3a3, m3a4, m3b1, m3b2, m3b3, m3b4, m3b5, m3b6;
 };
 
-// ---------------------------------------------------------------- fused inverse-xy + partner sums
-// A work-group owns one target t, one z-plane and one chunk of partners.  For
-// every partner it loads the z-stage outputs of the pair (xy still in G space),
-// finishes the 3D inverse transform with an in-LDS xy transform and accumulates
-// the pair's contributions for the N^2 points of its plane in registers.
-// Thread layout: RB rows x N columns; thread (y0, x) owns the points (y0 + RB i, x)
-// and, in the transform passes, one line.  Partner sums run in the working
-// precision inside a chunk (<= 64 partners) and in FP64 across chunks.
+struct FusedArgs {
+  int P, T, t0, S, chunk;     // orbitals, targets in batch, first target, partner chunks, partners per chunk
+};
+
+// index of the pair's shift in the kernel tables: k_jt - k_q (sign 1, target passes) or k_q - k_jt (sign 0)
+__device__ __forceinline__ int pair_dindex(const MeshInfo& mi, int jt, int q, int sign) {
+  const int kt = jt / mi.nb, kq = q / mi.nb;
+  return sign ? kindex_delta(mi, kt, kq) : kindex_delta(mi, kq, kt);
+}
+
+template <typename R>
+struct Basis {   // B_dc = component c of reciprocal row b_d, working precision
+  R b[9];
+};
+template <typename R>
+__device__ __forceinline__ Basis<R> basis(const Recip& rc) {
+  Basis<R> B;
+#pragma unroll
+  for (int i = 0; i < 9; ++i) B.b[i] = R(rc.b[i]);
+  return B;
+}
+// X_c = sum_d B_dc Y_d
+template <typename R>
+__device__ __forceinline__ void to_cart(const Basis<R>& B, const cx<R>* Y, cx<R>* X) {
+#pragma unroll
+  for (int c = 0; c < 3; ++c) X[c] = B.b[c] * Y[0] + B.b[3 + c] * Y[1] + B.b[6 + c] * Y[2];
+}
+// T_d = sum_c B_dc S_c
+template <typename R>
+__device__ __forceinline__ void to_latt(const Basis<R>& B, const cx<R>* S, cx<R>* T) {
+#pragma unroll
+  for (int d = 0; d < 3; ++d) T[d] = B.b[3 * d] * S[0] + B.b[3 * d + 1] * S[1] + B.b[3 * d + 2] * S[2];
+}
+
+template <typename R>
+__device__ __forceinline__ void cfma(cx<R>& acc, R a, cx<R> u, cx<R> v) {   // acc += a u v
+  const cx<R> p = u * v;
+  acc.x += a * p.x;
+  acc.y += a * p.y;
+}
+
+// Work-group layout of the plane kernels: RB rows x N columns of threads; thread (y0, x) owns the
+// plane points (y0 + RB i, x), i < N/RB, so loads and stores are coalesced along x and need no index
+// division, and in each transform pass it owns one line of one plane (up to RB planes per pass).
 template <typename R, int N>
 struct Fz {
   static constexpr int RB = (N % 8 == 0) ? 8 : 4;
-  static constexpr int NTH = RB * N;                                    // threads per work-group
-  static constexpr int KP = N / RB;                                     // owned points per thread
+  static constexpr int NTH = RB * N;
+  static constexpr int KP = N / RB;
   static constexpr int LD = N + 1;
-  static constexpr int PLANE = N * LD;                                  // LDS elements per plane
-  static constexpr int kBudget = 65536;
-  static constexpr int kFit = kBudget / int(PLANE * sizeof(cx<R>));
-  static constexpr int GRP0 = kFit < 1 ? 1 : kFit;
-  static constexpr int GRP = GRP0 < RB ? GRP0 : RB;                    // planes in LDS at once (<= RB lines/thread)
+  static constexpr int PLANE = N * LD;                     // LDS elements per plane
+  static constexpr int kLdsMax = 160 * 1024;               // LDS per work-group on gfx950
+  static constexpr bool fits(int planes) { return planes * PLANE * int(sizeof(cx<R>)) <= kLdsMax; }
+  static constexpr int kFitPlanes = kLdsMax / (PLANE * int(sizeof(cx<R>)));
+  static constexpr int GRP = kFitPlanes < RB ? kFitPlanes : RB;   // one-plane-per-partner rounds
 };
 
-// in-place 2D transform of np <= RB planes in LDS ([np][N][N+1]); ends with a barrier
+// in-place 2D transform of np planes in LDS ([np][N][N+1]); thread row p takes planes p, p + RB, ...;
+// ends with a barrier
 template <typename R, int N, int DIR>
 __device__ __forceinline__ void planes_fft(cx<R>* sm, int np, int tid) {
-  constexpr int LD = N + 1;
-  const int p = tid / N, l = tid - (tid / N) * N;
-  const bool act = p < np;
-  if (act) {
+  constexpr int LD = N + 1, RB = Fz<R, N>::RB;
+  const int p0 = tid / N, l = tid - (tid / N) * N;
+  for (int p = p0; p < np; p += RB) {
     cx<R> v[N];
     cx<R>* row = sm + (p * N + l) * LD;
 #pragma unroll
@@ -444,7 +327,7 @@ __device__ __forceinline__ void planes_fft(cx<R>* sm, int np, int tid) {
     for (int x = 0; x < N; ++x) row[x] = v[x];
   }
   __syncthreads();
-  if (act) {
+  for (int p = p0; p < np; p += RB) {
     cx<R> v[N];
     cx<R>* col = sm + p * N * LD + l;
 #pragma unroll
@@ -456,91 +339,336 @@ __device__ __forceinline__ void planes_fft(cx<R>* sm, int np, int tid) {
   __syncthreads();
 }
 
-struct FusedArgs {
-  int P, T, t0, S, chunk;     // orbitals, targets in batch, first target, partner chunks, partners per chunk
+// common decoding of a plane-kernel work-group
+template <typename R, int N>
+struct PlaneWG {
+  int x, y0, c, z, t, qb, qe;
+  long zo;    // global offset of owned point i: zo + RB N i
+  int so0;    // LDS offset of owned point i: so0 + RB LD i
+  __device__ PlaneWG(const FusedArgs& fa) {
+    using F = Fz<R, N>;
+    const int tid = threadIdx.x;
+    x = tid % N;
+    y0 = tid / N;
+    c = blockIdx.x % fa.S;
+    z = (blockIdx.x / fa.S) % N;
+    t = blockIdx.x / (fa.S * N);
+    qb = c * fa.chunk;
+    qe = min(fa.P, qb + fa.chunk);
+    zo = long(z) * N * N + y0 * N + x;
+    so0 = y0 * F::LD + x;
+  }
 };
 
-template <typename R>
-__device__ __forceinline__ void cfma(cx<R>& acc, R a, cx<R> u, cx<R> v) {   // acc += a u v
-  const cx<R> p = u * v;
-  acc.x += a * p.x;
-  acc.y += a * p.y;
-}
-
-// Pass A: buf7 per pair [XV, XU_par(3), XU_anti(3)] (xy in G space).  Slots:
-//   0: -m2ax w XV psi_q          (2ax)
-//   1: -m2bx1 w XU . D_q         (2bx1)
-//   2: -m3a4 w H3a4_q . XU       (2 x 3a4)
-//   h4 += w XU psi_q             (h4 of Alg. 3a3)
-// and, if do3b6, writes the 3b6 sources S_{s,c} = X^{U,s}_c n, forward xy transformed.
-template <typename R, int N>
-__global__ void __launch_bounds__((Fz<R, N>::NTH)) k_fused_A(const cx<R>* buf7, const cx<R>* psi, const cx<R>* D,
-                                                           const cx<R>* H3a4, const cx<R>* n, const double* w,
-                                                           FusedArgs fa, Masks m, int do3b6, cx<R>* src6,
-                                                           cx<R>* gpart, cx<R>* h4part) {
+// Pair densities rho = conj(psi_a) psi_b, forward xy transformed, for the pairs (t, q) of a target
+// batch: TFIRST (occupied pass) a = t0 + t, b = q; else a = q, b = t0 + t.  out[(t P + q)][N^3].
+template <typename R, int N, bool TFIRST>
+__global__ void __launch_bounds__((Fz<R, N>::NTH)) k_pair_xy(const cx<R>* psi, FusedArgs fa, cx<R>* out) {
   using F = Fz<R, N>;
-  constexpr int NN = N * N, KP = F::KP, RB = F::RB;
+  constexpr int KP = F::KP, RB = F::RB;
   constexpr long NR = long(N) * N * N;
   __shared__ cx<R> sm[F::GRP * F::PLANE];
-  const int tid = threadIdx.x;
-  const int x = tid % N, y0 = tid / N;
-  const int c = blockIdx.x % fa.S;
-  const int z = (blockIdx.x / fa.S) % N;
-  const int t = blockIdx.x / (fa.S * N);
-  const int qb = c * fa.chunk, qe = min(fa.P, qb + fa.chunk);
-  const long zo = long(z) * NN + y0 * N + x;      // global offset of owned point i: zo + RB*N*i
-  const int so0 = y0 * F::LD + x;                 // LDS offset of owned point i: so0 + RB*LD*i
+  const PlaneWG<R, N> wg(fa);
+  cx<R> pt[KP];
+#pragma unroll
+  for (int i = 0; i < KP; ++i) pt[i] = psi[long(fa.t0 + wg.t) * NR + wg.zo + RB * N * i];
+  for (int q0 = wg.qb; q0 < wg.qe; q0 += F::GRP) {
+    const int nq = min(F::GRP, wg.qe - q0);
+    for (int cc = 0; cc < nq; ++cc) {
+      const cx<R>* pq = psi + long(q0 + cc) * NR + wg.zo;
+#pragma unroll
+      for (int i = 0; i < KP; ++i)
+        sm[cc * F::PLANE + wg.so0 + RB * F::LD * i] = TFIRST ? cmulc(pt[i], pq[RB * N * i]) : cmulc(pq[RB * N * i], pt[i]);
+    }
+    __syncthreads();
+    planes_fft<R, N, -1>(sm, nq, threadIdx.x);
+    for (int cc = 0; cc < nq; ++cc) {
+      cx<R>* dst = out + (long(wg.t) * fa.P + q0 + cc) * NR + wg.zo;
+#pragma unroll
+      for (int i = 0; i < KP; ++i) dst[RB * N * i] = sm[cc * F::PLANE + wg.so0 + RB * F::LD * i];
+    }
+    __syncthreads();
+  }
+}
+
+// Pass-B sources of the pairs (t, q): Y_c = conj(psi_q) Z_tc + m3b5 conj(H3a4_qc) psi_t (TC mode:
+// H3b = conj(H3a4)); Z holds m2bx2 D_j - m3b3 h1 psi_j + m3b4 h4_j.  In lattice components
+// T_d = sum_c B_dc Y_c, forward xy transformed: out[(pair 2 + 0)] = kappa_1 T~_1 + kappa_2 T~_2,
+// out[(pair 2 + 1)] = T~_3, pair = t P + q, Delta = k_t - k_q.
+template <typename R, int N>
+__global__ void __launch_bounds__((Fz<R, N>::NTH)) k_passB_xy(const cx<R>* psi, const cx<R>* Z, const cx<R>* H3a4,
+                                                            FusedArgs fa, MeshInfo mi, Recip rc, const double* dfr,
+                                                            R m3b5, cx<R>* out) {
+  using F = Fz<R, N>;
+  constexpr int KP = F::KP, RB = F::RB;
+  constexpr int NPQ = F::GRP / 3 < 1 ? 1 : F::GRP / 3;   // partners per LDS round (three planes each)
+  constexpr long NR = long(N) * N * N;
+  __shared__ cx<R> sm[3 * NPQ * F::PLANE];
+  const PlaneWG<R, N> wg(fa);
+  const Basis<R> B = basis<R>(rc);
+  const long jt = fa.t0 + wg.t;
+  cx<R> zt[KP][3], pt[KP];
+#pragma unroll
+  for (int i = 0; i < KP; ++i) {
+    const long r = wg.zo + RB * N * i;
+    pt[i] = psi[jt * NR + r];
+#pragma unroll
+    for (int cc = 0; cc < 3; ++cc) zt[i][cc] = Z[(long(wg.t) * 3 + cc) * NR + r];
+  }
+  for (int q0 = wg.qb; q0 < wg.qe; q0 += NPQ) {
+    const int nq = min(NPQ, wg.qe - q0);
+    for (int a = 0; a < nq; ++a) {
+      const int q = q0 + a;
+#pragma unroll
+      for (int i = 0; i < KP; ++i) {
+        const long r = wg.zo + RB * N * i;
+        const cx<R> pq = psi[long(q) * NR + r];
+        cx<R> Y[3], T[3];
+#pragma unroll
+        for (int cc = 0; cc < 3; ++cc) {
+          Y[cc] = cmulc(pq, zt[i][cc]);
+          if (m3b5 != R(0)) Y[cc] = Y[cc] + m3b5 * cmulc(H3a4[(long(q) * 3 + cc) * NR + r], pt[i]);
+        }
+        to_latt(B, Y, T);
+#pragma unroll
+        for (int d = 0; d < 3; ++d) sm[(3 * a + d) * F::PLANE + wg.so0 + RB * F::LD * i] = T[d];
+      }
+    }
+    __syncthreads();
+    planes_fft<R, N, -1>(sm, 3 * nq, threadIdx.x);
+    for (int a = 0; a < nq; ++a) {
+      const int q = q0 + a;
+      const double* del = dfr + 3 * pair_dindex(mi, int(jt), q, 1);
+      const R k1 = R(double(mfreq<N>(wg.x)) + del[0]);
+      cx<R>* dst = out + (long(wg.t) * fa.P + q) * 2 * NR + wg.zo;
+#pragma unroll
+      for (int i = 0; i < KP; ++i) {
+        const int so = (3 * a) * F::PLANE + wg.so0 + RB * F::LD * i;
+        const R k2 = R(double(mfreq<N>(wg.y0 + RB * i)) + del[1]);
+        dst[RB * N * i] = k1 * sm[so] + k2 * sm[so + F::PLANE];
+        dst[NR + RB * N * i] = sm[so + 2 * F::PLANE];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// z stage of a pair convolution: forward z transform of the inputs, kernel multiply at Q = Delta + G
+// for the pair's Delta, inverse z transform of each output (one thread per (pair, x, y) column).
+//   OP_O : 1 -> 4  [W0_par, W3_par, W0_anti, W3_anti]
+//   OP_A1: 1 -> 5  [V2a_par rho, W0_par, W3_par, W0_anti, W3_anti]
+//          W0_s = u~_s rho, W3_s = i kappa_3 u~_s rho
+//   OP_A2: 4 -> 1  -i sum_s u~_s (P_s + kappa_3 R_s), inputs [P_par, R_par, P_anti, R_anti]
+//   OP_B : 2 -> 1  +i u~_par (P + kappa_3 R), inputs [P, R]
+template <int OP>
+struct OpShape;
+template <> struct OpShape<OP_A1> { static constexpr int nin = 1, nout = 5; };
+template <> struct OpShape<OP_O> { static constexpr int nin = 1, nout = 4; };
+template <> struct OpShape<OP_A2> { static constexpr int nin = 4, nout = 1; };
+template <> struct OpShape<OP_B> { static constexpr int nin = 2, nout = 1; };
+
+template <typename R, int N, int OP>
+__global__ void __launch_bounds__(256) k_zconv(const cx<R>* in, cx<R>* out, long npairs, int t0, MeshInfo mi,
+                                               Tables tb, int sign_target_minus_partner) {
+  constexpr int NN = N * N;
+  constexpr long NR = long(N) * N * N;
+  constexpr int NIN = OpShape<OP>::nin, NOUT = OpShape<OP>::nout;
+  const long col = long(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (col >= npairs * NN) return;
+  const long pair = col / NN;
+  const int xy = int(col - pair * NN);
+  const int t = int(pair / mi.P), q = int(pair - long(t) * mi.P);
+  const int di = pair_dindex(mi, t0 + t, q, sign_target_minus_partner);
+  const R* tV = reinterpret_cast<const R*>(tb.V) + long(di) * NR + xy;
+  const R* tU[2] = {reinterpret_cast<const R*>(tb.U1) + long(di) * NR + xy,
+                    reinterpret_cast<const R*>(tb.U2) + long(di) * NR + xy};
+  const R d3 = R(tb.dfr[3 * di + 2]);   // kappa_3(z) = m_z + delta_3
+
+  if constexpr (NIN == 1) {
+    cx<R> acc[N], v[N];
+    const cx<R>* b = in + pair * NR + xy;
+#pragma unroll
+    for (int z = 0; z < N; ++z) acc[z] = b[z * NN];
+    fft_line<R, N, -1>(acc);
+    cx<R>* o = out + pair * NOUT * NR + xy;
+    if constexpr (OP == OP_A1) {
+#pragma unroll
+      for (int z = 0; z < N; ++z) v[z] = tV[z * NN] * acc[z];
+      fft_line<R, N, 1>(v);
+#pragma unroll
+      for (int z = 0; z < N; ++z) o[z * NN] = v[z];
+      o += NR;
+    }
+#pragma unroll 1
+    for (int s = 0; s < 2; ++s) {
+      R u[N];
+#pragma unroll
+      for (int z = 0; z < N; ++z) u[z] = tU[s][z * NN];
+#pragma unroll
+      for (int z = 0; z < N; ++z) v[z] = u[z] * acc[z];
+      fft_line<R, N, 1>(v);
+#pragma unroll
+      for (int z = 0; z < N; ++z) o[z * NN] = v[z];
+#pragma unroll
+      for (int z = 0; z < N; ++z) v[z] = mul_i(((R(mfreq<N>(z)) + d3) * u[z]) * acc[z]);
+      fft_line<R, N, 1>(v);
+#pragma unroll
+      for (int z = 0; z < N; ++z) o[NR + z * NN] = v[z];
+      o += 2 * NR;
+    }
+  } else {
+    cx<R> acc[N], v[N];
+#pragma unroll
+    for (int z = 0; z < N; ++z) acc[z] = mk<R>(R(0), R(0));
+#pragma unroll 1
+    for (int s = 0; s < NIN / 2; ++s) {
+      const cx<R>* b = in + (pair * NIN + 2 * s) * NR + xy;
+#pragma unroll
+      for (int z = 0; z < N; ++z) v[z] = b[z * NN];
+      fft_line<R, N, -1>(v);
+#pragma unroll
+      for (int z = 0; z < N; ++z) acc[z] = acc[z] + tU[s][z * NN] * v[z];
+#pragma unroll
+      for (int z = 0; z < N; ++z) v[z] = b[NR + z * NN];
+      fft_line<R, N, -1>(v);
+#pragma unroll
+      for (int z = 0; z < N; ++z) acc[z] = acc[z] + ((R(mfreq<N>(z)) + d3) * tU[s][z * NN]) * v[z];
+    }
+#pragma unroll
+    for (int z = 0; z < N; ++z) acc[z] = OP == OP_A2 ? mul_i(R(-1) * acc[z]) : mul_i(acc[z]);
+    fft_line<R, N, 1>(acc);
+    cx<R>* o = out + pair * NR + xy;
+#pragma unroll
+    for (int z = 0; z < N; ++z) o[z * NN] = acc[z];
+  }
+}
+
+// Pass A, fused inverse xy + partner sums.  buf5 per pair (xy in G space):
+// [XV, W0_par, W3_par, W0_anti, W3_anti].  With X^U the Cartesian vector fields, accumulates for the
+// owned points of target t over the chunk's partners q:
+//   slot 0: -m2ax w XV psi_q          (2ax)
+//   slot 1: -m2bx1 w X^U_par . D_q     (2bx1)
+//   slot 2: -m3a4 w H3a4_q . X^U_par   (2 x 3a4)
+//   h4    : w X^U_par psi_q            (h4 of Alg. 3a3)
+// and, if do3b6, writes the 3b6 sources S_s,c = X^U_s,c n in the forward split form
+// src4 per pair [P_par, R_par, P_anti, R_anti].  Delta = k_t - k_q.
+template <typename R, int N>
+struct PassA {
+  static constexpr bool SPLIT = !Fz<R, N>::fits(7);   // spin channels in separate LDS rounds
+  static constexpr int NPL = SPLIT ? 4 : 7;
+};
+
+template <typename R, int N>
+__global__ void __launch_bounds__((Fz<R, N>::NTH)) k_fused_A(const cx<R>* buf5, const cx<R>* psi, const cx<R>* D,
+                                                           const cx<R>* H3a4, const cx<R>* n, const double* w,
+                                                           FusedArgs fa, Masks m, int do3b6, MeshInfo mi, Recip rc,
+                                                           const double* dfr, cx<R>* src4, cx<R>* gpart,
+                                                           cx<R>* h4part) {
+  using F = Fz<R, N>;
+  constexpr int KP = F::KP, RB = F::RB, PL = F::PLANE;
+  constexpr bool SPLIT = PassA<R, N>::SPLIT;
+  constexpr long NR = long(N) * N * N;
+  __shared__ cx<R> sm[PassA<R, N>::NPL * PL];
+  const PlaneWG<R, N> wg(fa);
+  const Basis<R> B = basis<R>(rc);
+  const int jt = fa.t0 + wg.t;
   cx<R> ga[KP][3], h4[KP][3], nk[KP];
 #pragma unroll
   for (int i = 0; i < KP; ++i) {
 #pragma unroll
     for (int s = 0; s < 3; ++s) ga[i][s] = h4[i][s] = mk<R>(R(0), R(0));
-    nk[i] = n[zo + RB * N * i];
+    nk[i] = n[wg.zo + RB * N * i];
   }
   const R a0 = R(-m.m2ax), a1 = R(-m.m2bx1), a2 = R(-m.m3a4);
-  for (int q = qb; q < qe; ++q) {
+  for (int q = wg.qb; q < wg.qe; ++q) {
     const R wq = R(w[q]);
-    const long pair = long(t) * fa.P + q;
-    for (int c0 = 0; c0 < 7; c0 += F::GRP) {
-      const int nc = min(F::GRP, 7 - c0);
-      for (int cc = 0; cc < nc; ++cc) {
-        const cx<R>* src = buf7 + (pair * 7 + c0 + cc) * NR + zo;
-#pragma unroll
-        for (int i = 0; i < KP; ++i) sm[cc * F::PLANE + so0 + RB * F::LD * i] = src[RB * N * i];
-      }
-      __syncthreads();
-      planes_fft<R, N, 1>(sm, nc, tid);
+    const long pair = long(wg.t) * fa.P + q;
+    const double* del = dfr + 3 * pair_dindex(mi, jt, q, 1);
+    const R k1 = R(double(mfreq<N>(wg.x)) + del[0]);
+    const cx<R>* src = buf5 + pair * 5 * NR + wg.zo;
+#pragma unroll 1
+    for (int g = 0; g < (SPLIT ? 2 : 1); ++g) {
+      const bool par = !SPLIT || g == 0, anti = !SPLIT || g == 1;
+      const int ab = SPLIT ? 0 : 4;   // LDS slot of Y_anti,1
+      // load: slot 0 XV, slots 1-3 Y_par, slots ab..ab+2 Y_anti
 #pragma unroll
       for (int i = 0; i < KP; ++i) {
-        const long r = zo + RB * N * i;
-        const int so = so0 + RB * F::LD * i;
-        const cx<R> pq = psi[long(q) * NR + r];
+        const int so = wg.so0 + RB * F::LD * i;
+        const long o = RB * N * i;
+        const R k2 = R(double(mfreq<N>(wg.y0 + RB * i)) + del[1]);
+        if (par) {
+          sm[so] = src[o];
+          const cx<R> w0 = src[NR + o];
+          sm[PL + so] = mul_i(k1 * w0);
+          sm[2 * PL + so] = mul_i(k2 * w0);
+          sm[3 * PL + so] = src[2 * NR + o];
+        }
+        if (anti) {
+          const cx<R> w0 = src[3 * NR + o];
+          sm[ab * PL + so] = mul_i(k1 * w0);
+          sm[(ab + 1) * PL + so] = mul_i(k2 * w0);
+          sm[(ab + 2) * PL + so] = src[4 * NR + o];
+        }
+      }
+      __syncthreads();
+      planes_fft<R, N, 1>(sm, SPLIT ? (g == 0 ? 4 : 3) : 7, threadIdx.x);
 #pragma unroll
-        for (int comp = 0; comp < 7; ++comp) {
-          if (comp < c0 || comp >= c0 + nc) continue;
-          cx<R>* slot = sm + (comp - c0) * F::PLANE + so;
-          const cx<R> X = *slot;
-          if (comp == 0) {
-            cfma(ga[i][0], a0 * wq, X, pq);
-          } else if (comp <= 3) {
-            const int cd = comp - 1;
-            cfma(ga[i][1], a1 * wq, X, D[(long(cd) * fa.P + q) * NR + r]);
-            cfma(ga[i][2], a2 * wq, X, H3a4[(long(q) * 3 + cd) * NR + r]);
-            cfma(h4[i][cd], wq, X, pq);
-            *slot = X * nk[i];
-          } else {
-            *slot = X * nk[i];
+      for (int i = 0; i < KP; ++i) {
+        const long r = wg.zo + RB * N * i;
+        const int so = wg.so0 + RB * F::LD * i;
+        if (par) {
+          const cx<R> pq = psi[long(q) * NR + r];
+          cfma(ga[i][0], a0 * wq, sm[so], pq);
+          cx<R> Y[3], X[3];
+#pragma unroll
+          for (int d = 0; d < 3; ++d) Y[d] = sm[(1 + d) * PL + so];
+          to_cart(B, Y, X);
+#pragma unroll
+          for (int cd = 0; cd < 3; ++cd) {
+            cfma(ga[i][1], a1 * wq, X[cd], D[(long(cd) * fa.P + q) * NR + r]);
+            cfma(ga[i][2], a2 * wq, X[cd], H3a4[(long(q) * 3 + cd) * NR + r]);
+            cfma(h4[i][cd], wq, X[cd], pq);
           }
+          if (do3b6) {
+            cx<R> S[3], T[3];
+#pragma unroll
+            for (int cd = 0; cd < 3; ++cd) S[cd] = X[cd] * nk[i];
+            to_latt(B, S, T);
+#pragma unroll
+            for (int d = 0; d < 3; ++d) sm[(1 + d) * PL + so] = T[d];
+          }
+        }
+        if (anti && do3b6) {
+          cx<R> Y[3], X[3], S[3], T[3];
+#pragma unroll
+          for (int d = 0; d < 3; ++d) Y[d] = sm[(ab + d) * PL + so];
+          to_cart(B, Y, X);
+#pragma unroll
+          for (int cd = 0; cd < 3; ++cd) S[cd] = X[cd] * nk[i];
+          to_latt(B, S, T);
+#pragma unroll
+          for (int d = 0; d < 3; ++d) sm[(ab + d) * PL + so] = T[d];
         }
       }
       __syncthreads();
       if (do3b6) {
-        const int s0 = c0 == 0 ? 1 : 0;     // component 0 (XV) has no 3b6 source
-        planes_fft<R, N, -1>(sm + s0 * F::PLANE, nc - s0, tid);
-        for (int cc = s0; cc < nc; ++cc) {
-          cx<R>* dst = src6 + (pair * 6 + c0 + cc - 1) * NR + zo;
+        // forward xy of the T planes (slots 1..6 unsplit; 1..3 or 0..2 split), then the split form
+        const int s0 = (SPLIT && g == 1) ? 0 : 1;
+        planes_fft<R, N, -1>(sm + s0 * PL, SPLIT ? 3 : 6, threadIdx.x);
+        cx<R>* dst = src4 + pair * 4 * NR + wg.zo;
 #pragma unroll
-          for (int i = 0; i < KP; ++i) dst[RB * N * i] = sm[cc * F::PLANE + so0 + RB * F::LD * i];
+        for (int i = 0; i < KP; ++i) {
+          const int so = wg.so0 + RB * F::LD * i;
+          const long o = RB * N * i;
+          const R k2 = R(double(mfreq<N>(wg.y0 + RB * i)) + del[1]);
+          if (par) {
+            dst[o] = k1 * sm[PL + so] + k2 * sm[2 * PL + so];
+            dst[NR + o] = sm[3 * PL + so];
+          }
+          if (anti) {
+            dst[2 * NR + o] = k1 * sm[ab * PL + so] + k2 * sm[(ab + 1) * PL + so];
+            dst[3 * NR + o] = sm[(ab + 2) * PL + so];
+          }
         }
         __syncthreads();
       }
@@ -548,77 +676,71 @@ __global__ void __launch_bounds__((Fz<R, N>::NTH)) k_fused_A(const cx<R>* buf7, 
   }
 #pragma unroll
   for (int i = 0; i < KP; ++i) {
-    const long r = zo + RB * N * i;
+    const long r = wg.zo + RB * N * i;
 #pragma unroll
     for (int s = 0; s < 3; ++s) {
-      gpart[((long(c) * fa.T + t) * 3 + s) * NR + r] = ga[i][s];
-      h4part[((long(c) * fa.T + t) * 3 + s) * NR + r] = h4[i][s];
+      gpart[((long(wg.c) * fa.T + wg.t) * 3 + s) * NR + r] = ga[i][s];
+      h4part[((long(wg.c) * fa.T + wg.t) * 3 + s) * NR + r] = h4[i][s];
     }
   }
 }
 
-// One field per pair (xy in G space): partial of coef sum_q w_q Y psi_q.  GRP partners at a time.
+// One field per pair (xy in G space): partial of coef sum_q w_q Y psi_q, GRP partners per round.
 template <typename R, int N>
 __global__ void __launch_bounds__((Fz<R, N>::NTH)) k_fused_Y(const cx<R>* buf1, const cx<R>* psi, const double* w,
                                                            FusedArgs fa, double coef, cx<R>* gpart) {
   using F = Fz<R, N>;
-  constexpr int NN = N * N, KP = F::KP, RB = F::RB;
+  constexpr int KP = F::KP, RB = F::RB;
   constexpr long NR = long(N) * N * N;
   __shared__ cx<R> sm[F::GRP * F::PLANE];
-  const int tid = threadIdx.x;
-  const int x = tid % N, y0 = tid / N;
-  const int c = blockIdx.x % fa.S;
-  const int z = (blockIdx.x / fa.S) % N;
-  const int t = blockIdx.x / (fa.S * N);
-  const int qb = c * fa.chunk, qe = min(fa.P, qb + fa.chunk);
-  const long zo = long(z) * NN + y0 * N + x;
-  const int so0 = y0 * F::LD + x;
+  const PlaneWG<R, N> wg(fa);
   cx<R> ga[KP];
 #pragma unroll
   for (int i = 0; i < KP; ++i) ga[i] = mk<R>(R(0), R(0));
-  for (int q0 = qb; q0 < qe; q0 += F::GRP) {
-    const int nq = min(F::GRP, qe - q0);
+  for (int q0 = wg.qb; q0 < wg.qe; q0 += F::GRP) {
+    const int nq = min(F::GRP, wg.qe - q0);
     for (int cc = 0; cc < nq; ++cc) {
-      const cx<R>* src = buf1 + (long(t) * fa.P + q0 + cc) * NR + zo;
+      const cx<R>* src = buf1 + (long(wg.t) * fa.P + q0 + cc) * NR + wg.zo;
 #pragma unroll
-      for (int i = 0; i < KP; ++i) sm[cc * F::PLANE + so0 + RB * F::LD * i] = src[RB * N * i];
+      for (int i = 0; i < KP; ++i) sm[cc * F::PLANE + wg.so0 + RB * F::LD * i] = src[RB * N * i];
     }
     __syncthreads();
-    planes_fft<R, N, 1>(sm, nq, tid);
+    planes_fft<R, N, 1>(sm, nq, threadIdx.x);
 #pragma unroll
     for (int i = 0; i < KP; ++i) {
-      const long r = zo + RB * N * i;
-      const int so = so0 + RB * F::LD * i;
-#pragma unroll
-      for (int cc = 0; cc < F::GRP; ++cc) {
-        if (cc >= nq) continue;
+      const long r = wg.zo + RB * N * i;
+      const int so = wg.so0 + RB * F::LD * i;
+      for (int cc = 0; cc < nq; ++cc)
         cfma(ga[i], R(coef * w[q0 + cc]), sm[cc * F::PLANE + so], psi[long(q0 + cc) * NR + r]);
-      }
     }
     __syncthreads();
   }
 #pragma unroll
-  for (int i = 0; i < KP; ++i) gpart[(long(c) * fa.T + t) * NR + zo + RB * N * i] = ga[i];
+  for (int i = 0; i < KP; ++i) gpart[(long(wg.c) * fa.T + wg.t) * NR + wg.zo + RB * N * i] = ga[i];
 }
 
-// Occupied-occupied pass: buf6 per pair (a = t0+t, b = q) [V_par(3), V_anti(3)], xy in G space.
+// Occupied-occupied pass: buf4 per pair (a = t0 + t, b = q; Delta = k_b - k_a), xy in G space:
+// [W0_par, W3_par, W0_anti, W3_anti].  With V_s the Cartesian vector fields:
 //   h5[a]   += w_b (|V_par|^2 + |V_anti|^2)     (Alg. 3a2; TC mode: V_ba = conj(V_ab))
 //   H3a4[a] += w_b conj(V_par) psi_b            (Alg. 3a4 h3; Alg. 3b2 h3 is its conjugate)
 template <typename R, int N>
-__global__ void __launch_bounds__((Fz<R, N>::NTH)) k_fused_O(const cx<R>* buf6, const cx<R>* psi, const double* w,
-                                                           FusedArgs fa, R* h5part, cx<R>* H3part) {
+struct PassO {
+  static constexpr bool SPLIT = !Fz<R, N>::fits(6);
+  static constexpr int NPL = SPLIT ? 3 : 6;
+};
+
+template <typename R, int N>
+__global__ void __launch_bounds__((Fz<R, N>::NTH)) k_fused_O(const cx<R>* buf4, const cx<R>* psi, const double* w,
+                                                           FusedArgs fa, MeshInfo mi, Recip rc, const double* dfr,
+                                                           R* h5part, cx<R>* H3part) {
   using F = Fz<R, N>;
-  constexpr int NN = N * N, KP = F::KP, RB = F::RB;
+  constexpr int KP = F::KP, RB = F::RB, PL = F::PLANE;
+  constexpr bool SPLIT = PassO<R, N>::SPLIT;
   constexpr long NR = long(N) * N * N;
-  __shared__ cx<R> sm[F::GRP * F::PLANE];
-  const int tid = threadIdx.x;
-  const int x = tid % N, y0 = tid / N;
-  const int c = blockIdx.x % fa.S;
-  const int z = (blockIdx.x / fa.S) % N;
-  const int t = blockIdx.x / (fa.S * N);
-  const int qb = c * fa.chunk, qe = min(fa.P, qb + fa.chunk);
-  const long zo = long(z) * NN + y0 * N + x;
-  const int so0 = y0 * F::LD + x;
+  __shared__ cx<R> sm[PassO<R, N>::NPL * PL];
+  const PlaneWG<R, N> wg(fa);
+  const Basis<R> B = basis<R>(rc);
+  const int ja = fa.t0 + wg.t;
   R h5[KP];
   cx<R> H[KP][3];
 #pragma unroll
@@ -626,33 +748,60 @@ __global__ void __launch_bounds__((Fz<R, N>::NTH)) k_fused_O(const cx<R>* buf6, 
     h5[i] = R(0);
     H[i][0] = H[i][1] = H[i][2] = mk<R>(R(0), R(0));
   }
-  for (int q = qb; q < qe; ++q) {
+  for (int q = wg.qb; q < wg.qe; ++q) {
     const R wq = R(w[q]);
-    const long pair = long(t) * fa.P + q;
-    for (int c0 = 0; c0 < 6; c0 += F::GRP) {
-      const int nc = min(F::GRP, 6 - c0);
-      for (int cc = 0; cc < nc; ++cc) {
-        const cx<R>* src = buf6 + (pair * 6 + c0 + cc) * NR + zo;
-#pragma unroll
-        for (int i = 0; i < KP; ++i) sm[cc * F::PLANE + so0 + RB * F::LD * i] = src[RB * N * i];
-      }
-      __syncthreads();
-      planes_fft<R, N, 1>(sm, nc, tid);
+    const long pair = long(wg.t) * fa.P + q;
+    const double* del = dfr + 3 * pair_dindex(mi, ja, q, 0);
+    const R k1 = R(double(mfreq<N>(wg.x)) + del[0]);
+    const cx<R>* src = buf4 + pair * 4 * NR + wg.zo;
+#pragma unroll 1
+    for (int g = 0; g < (SPLIT ? 2 : 1); ++g) {
+      const bool par = !SPLIT || g == 0, anti = !SPLIT || g == 1;
+      const int ab = SPLIT ? 0 : 3;
 #pragma unroll
       for (int i = 0; i < KP; ++i) {
-        const long r = zo + RB * N * i;
-        const int so = so0 + RB * F::LD * i;
-        const cx<R> pq = psi[long(q) * NR + r];
+        const int so = wg.so0 + RB * F::LD * i;
+        const long o = RB * N * i;
+        const R k2 = R(double(mfreq<N>(wg.y0 + RB * i)) + del[1]);
+        if (par) {
+          const cx<R> w0 = src[o];
+          sm[so] = mul_i(k1 * w0);
+          sm[PL + so] = mul_i(k2 * w0);
+          sm[2 * PL + so] = src[NR + o];
+        }
+        if (anti) {
+          const cx<R> w0 = src[2 * NR + o];
+          sm[ab * PL + so] = mul_i(k1 * w0);
+          sm[(ab + 1) * PL + so] = mul_i(k2 * w0);
+          sm[(ab + 2) * PL + so] = src[3 * NR + o];
+        }
+      }
+      __syncthreads();
+      planes_fft<R, N, 1>(sm, SPLIT ? 3 : 6, threadIdx.x);
 #pragma unroll
-        for (int comp = 0; comp < 6; ++comp) {
-          if (comp < c0 || comp >= c0 + nc) continue;
-          const cx<R> V = sm[(comp - c0) * F::PLANE + so];
-          h5[i] += wq * (V.x * V.x + V.y * V.y);
-          if (comp < 3) {
-            const cx<R> hv = cmulc(V, pq);
-            H[i][comp].x += wq * hv.x;
-            H[i][comp].y += wq * hv.y;
+      for (int i = 0; i < KP; ++i) {
+        const long r = wg.zo + RB * N * i;
+        const int so = wg.so0 + RB * F::LD * i;
+        cx<R> Y[3], X[3];
+        if (par) {
+          const cx<R> pq = psi[long(q) * NR + r];
+#pragma unroll
+          for (int d = 0; d < 3; ++d) Y[d] = sm[d * PL + so];
+          to_cart(B, Y, X);
+#pragma unroll
+          for (int cd = 0; cd < 3; ++cd) {
+            h5[i] += wq * (X[cd].x * X[cd].x + X[cd].y * X[cd].y);
+            const cx<R> hv = cmulc(X[cd], pq);
+            H[i][cd].x += wq * hv.x;
+            H[i][cd].y += wq * hv.y;
           }
+        }
+        if (anti) {
+#pragma unroll
+          for (int d = 0; d < 3; ++d) Y[d] = sm[(ab + d) * PL + so];
+          to_cart(B, Y, X);
+#pragma unroll
+          for (int cd = 0; cd < 3; ++cd) h5[i] += wq * (X[cd].x * X[cd].x + X[cd].y * X[cd].y);
         }
       }
       __syncthreads();
@@ -660,10 +809,10 @@ __global__ void __launch_bounds__((Fz<R, N>::NTH)) k_fused_O(const cx<R>* buf6, 
   }
 #pragma unroll
   for (int i = 0; i < KP; ++i) {
-    const long r = zo + RB * N * i;
-    h5part[(long(c) * fa.T + t) * NR + r] = h5[i];
+    const long r = wg.zo + RB * N * i;
+    h5part[(long(wg.c) * fa.T + wg.t) * NR + r] = h5[i];
 #pragma unroll
-    for (int cd = 0; cd < 3; ++cd) H3part[((long(c) * fa.T + t) * 3 + cd) * NR + r] = H[i][cd];
+    for (int cd = 0; cd < 3; ++cd) H3part[((long(wg.c) * fa.T + wg.t) * 3 + cd) * NR + r] = H[i][cd];
   }
 }
 
