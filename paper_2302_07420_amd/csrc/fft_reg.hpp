@@ -64,6 +64,27 @@ __device__ __forceinline__ cx<R> twiddle(int a) {
   return DIR < 0 ? w : conjg(w);
 }
 
+// v e^{DIR 2 pi i a / N}.  The index is a constant after unrolling: multiples of N/4 become sign
+// swaps and odd multiples of N/8 two additions and two multiplications; the rest use the table.
+template <typename R, int N, int DIR>
+__device__ __forceinline__ cx<R> twiddle_mul(cx<R> v, int a) {
+  a %= N;
+  if (a == 0) return v;
+  if (2 * a == N) return {-v.x, -v.y};
+  if (4 * a == N) return DIR < 0 ? cx<R>{v.y, -v.x} : cx<R>{-v.y, v.x};        // -i v : i v
+  if (4 * a == 3 * N) return DIR < 0 ? cx<R>{-v.y, v.x} : cx<R>{v.y, -v.x};    //  i v : -i v
+  if (N % 8 == 0 && (8 * a) % N == 0) {
+    // e^{DIR i pi t/4}, t odd: (c, s) with |c| = |s| = sqrt(1/2)
+    const int t = 8 * a / N;
+    const R h = R(0.70710678118654752440);
+    const R c = (t == 1 || t == 7) ? h : -h;
+    const R sn = R(DIR) * ((t == 1 || t == 3) ? h : -h);
+    if (c == sn) return {c * (v.x - v.y), c * (v.x + v.y)};
+    return {c * (v.x + v.y), c * (v.y - v.x)};
+  }
+  return v * twiddle<R, N, DIR>(a);
+}
+
 template <typename R, int DIR>
 __device__ __forceinline__ void dft2(cx<R>* v) {
   cx<R> a = v[0], b = v[1];
@@ -113,7 +134,7 @@ __device__ __forceinline__ void stage(cx<R>* x) {
 #pragma unroll
     for (int m = 0; m < RAD; ++m) {
       v[m] = x[j + m * (N / RAD)];
-      if (m * k != 0) v[m] = v[m] * twiddle<R, N, DIR>((m * k * (N / (NS * RAD))) % N);
+      if (m * k != 0) v[m] = twiddle_mul<R, N, DIR>(v[m], m * k * (N / (NS * RAD)));
     }
     dft<R, DIR, RAD>(v);
 #pragma unroll
@@ -129,15 +150,46 @@ __device__ __forceinline__ void stages(cx<R>* x) {
   if constexpr (sizeof...(REST) > 0) stages<R, N, DIR, NS * RAD, REST...>(x);
 }
 
+// Power-of-two lengths: Stockham stages (radix 4, then 2 or 4).
+template <typename R, int N, int DIR>
+__device__ __forceinline__ void fft_pow2(cx<R>* x) {
+  if constexpr (N == 4) dft4<R, DIR>(x);
+  else if constexpr (N == 8) stages<R, 8, DIR, 1, 4, 2>(x);
+  else if constexpr (N == 16) stages<R, 16, DIR, 1, 4, 4>(x);
+  else stages<R, 32, DIR, 1, 4, 4, 2>(x);
+}
+
+// Lengths 3 M (M = 4, 8, 16, coprime to 3): Good-Thomas prime-factor algorithm, no twiddles between
+// the two factors.  Input n = (M n1 + 3 n2) mod N goes to a[n1][n2]; M-point transforms along n2,
+// 3-point transforms along n1; output (k1, k2) is X[(M U k1 + 3 V k2) mod N] with U = M^-1 mod 3 and
+// V = 3^-1 mod M (Chinese remainder map).  All indices are compile-time constants after unrolling.
+template <typename R, int M, int DIR>
+__device__ __forceinline__ void fft_pfa3(cx<R>* x) {
+  constexpr int N = 3 * M;
+  constexpr int U = (M % 3 == 1) ? 1 : 2;
+  constexpr int V = (M == 4) ? 3 : (M == 8) ? 3 : 11;
+  static_assert((M * U) % 3 == 1 && (3 * V) % M == 1, "inverse residues");
+  cx<R> a[3][M];
+#pragma unroll
+  for (int n1 = 0; n1 < 3; ++n1) {
+#pragma unroll
+    for (int n2 = 0; n2 < M; ++n2) a[n1][n2] = x[(M * n1 + 3 * n2) % N];
+    fft_pow2<R, M, DIR>(a[n1]);
+  }
+#pragma unroll
+  for (int k2 = 0; k2 < M; ++k2) {
+    cx<R> t[3] = {a[0][k2], a[1][k2], a[2][k2]};
+    dft3<R, DIR>(t);
+#pragma unroll
+    for (int k1 = 0; k1 < 3; ++k1) x[(M * U * k1 + 3 * V * k2) % N] = t[k1];
+  }
+}
+
 template <typename R, int N, int DIR>
 __device__ __forceinline__ void fft_line(cx<R>* x) {
   static_assert(N == 8 || N == 12 || N == 16 || N == 24 || N == 32 || N == 48, "unsupported length");
-  if constexpr (N == 8) stages<R, 8, DIR, 1, 4, 2>(x);
-  else if constexpr (N == 12) stages<R, 12, DIR, 1, 4, 3>(x);
-  else if constexpr (N == 16) stages<R, 16, DIR, 1, 4, 4>(x);
-  else if constexpr (N == 24) stages<R, 24, DIR, 1, 4, 3, 2>(x);
-  else if constexpr (N == 32) stages<R, 32, DIR, 1, 4, 4, 2>(x);
-  else stages<R, 48, DIR, 1, 4, 4, 3>(x);
+  if constexpr (N == 12 || N == 24 || N == 48) fft_pfa3<R, N / 3, DIR>(x);
+  else fft_pow2<R, N, DIR>(x);
 }
 
 }  // namespace tcmi
