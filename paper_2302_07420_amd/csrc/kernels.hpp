@@ -395,8 +395,13 @@ __global__ void __launch_bounds__((Fz<R, N>::NTH)) k_pair_xy(const cx<R>* psi, F
 // H3b = conj(H3a4)); Z holds m2bx2 D_j - m3b3 h1 psi_j + m3b4 h4_j.  In lattice components
 // T_d = sum_c B_dc Y_c, forward xy transformed: out[(pair 2 + 0)] = kappa_1 T~_1 + kappa_2 T~_2,
 // out[(pair 2 + 1)] = T~_3, pair = t P + q, Delta = k_t - k_q.
+// occupancy target of k_passB_xy: 3 waves per SIMD where that costs no spills (FP32 at 24^3)
 template <typename R, int N>
-__global__ void __launch_bounds__((Fz<R, N>::NTH)) k_passB_xy(const cx<R>* psi, const cx<R>* Z, const cx<R>* H3a4,
+constexpr int kPassBWaves = (sizeof(R) == 4 && N == 24) ? 3 : 1;
+
+template <typename R, int N>
+__global__ void __launch_bounds__((Fz<R, N>::NTH)) __attribute__((amdgpu_waves_per_eu(kPassBWaves<R, N>)))
+k_passB_xy(const cx<R>* psi, const cx<R>* Z, const cx<R>* H3a4,
                                                             FusedArgs fa, MeshInfo mi, Recip rc, const double* dfr,
                                                             R m3b5, cx<R>* out) {
   using F = Fz<R, N>;
@@ -415,25 +420,41 @@ __global__ void __launch_bounds__((Fz<R, N>::NTH)) k_passB_xy(const cx<R>* psi, 
 #pragma unroll
     for (int cc = 0; cc < 3; ++cc) zt[i][cc] = Z[(long(wg.t) * 3 + cc) * NR + r];
   }
-  for (int q0 = wg.qb; q0 < wg.qe; q0 += NPQ) {
-    const int nq = min(NPQ, wg.qe - q0);
-    for (int a = 0; a < nq; ++a) {
-      const int q = q0 + a;
+  // partner fields psi_q, H3a4_q of the next round are loaded while this round is transformed
+  cx<R> pre[NPQ][4][KP];
+  auto fetch = [&](int q0) {
+#pragma unroll
+    for (int a = 0; a < NPQ; ++a) {
+      const int q = min(q0 + a, wg.qe - 1);
 #pragma unroll
       for (int i = 0; i < KP; ++i) {
         const long r = wg.zo + RB * N * i;
-        const cx<R> pq = psi[long(q) * NR + r];
+        pre[a][0][i] = psi[long(q) * NR + r];
+#pragma unroll
+        for (int cc = 0; cc < 3; ++cc) pre[a][1 + cc][i] = H3a4[(long(q) * 3 + cc) * NR + r];
+      }
+    }
+  };
+  if (wg.qb < wg.qe) fetch(wg.qb);
+  for (int q0 = wg.qb; q0 < wg.qe; q0 += NPQ) {
+    const int nq = min(NPQ, wg.qe - q0);
+#pragma unroll
+    for (int a = 0; a < NPQ; ++a) {
+      if (a >= nq) continue;
+#pragma unroll
+      for (int i = 0; i < KP; ++i) {
         cx<R> Y[3], T[3];
 #pragma unroll
         for (int cc = 0; cc < 3; ++cc) {
-          Y[cc] = cmulc(pq, zt[i][cc]);
-          if (m3b5 != R(0)) Y[cc] = Y[cc] + m3b5 * cmulc(H3a4[(long(q) * 3 + cc) * NR + r], pt[i]);
+          Y[cc] = cmulc(pre[a][0][i], zt[i][cc]);
+          if (m3b5 != R(0)) Y[cc] = Y[cc] + m3b5 * cmulc(pre[a][1 + cc][i], pt[i]);
         }
         to_latt(B, Y, T);
 #pragma unroll
         for (int d = 0; d < 3; ++d) sm[(3 * a + d) * F::PLANE + wg.so0 + RB * F::LD * i] = T[d];
       }
     }
+    if (q0 + NPQ < wg.qe) fetch(q0 + NPQ);
     __syncthreads();
     planes_fft<R, N, -1>(sm, 3 * nq, threadIdx.x);
     for (int a = 0; a < nq; ++a) {
@@ -580,6 +601,16 @@ __global__ void __launch_bounds__((Fz<R, N>::NTH)) k_fused_A(const cx<R>* buf5, 
     nk[i] = n[wg.zo + RB * N * i];
   }
   const R a0 = R(-m.m2ax), a1 = R(-m.m2bx1), a2 = R(-m.m3a4);
+  // the next partner's five pair planes are loaded into registers while this partner is transformed
+  cx<R> pre[5][KP];
+  auto fetch = [&](int q) {
+    const cx<R>* src = buf5 + (long(wg.t) * fa.P + q) * 5 * NR + wg.zo;
+#pragma unroll
+    for (int f = 0; f < 5; ++f)
+#pragma unroll
+      for (int i = 0; i < KP; ++i) pre[f][i] = src[f * NR + RB * N * i];
+  };
+  if (!SPLIT && wg.qb < wg.qe) fetch(wg.qb);
   for (int q = wg.qb; q < wg.qe; ++q) {
     const R wq = R(w[q]);
     const long pair = long(wg.t) * fa.P + q;
@@ -597,19 +628,20 @@ __global__ void __launch_bounds__((Fz<R, N>::NTH)) k_fused_A(const cx<R>* buf5, 
         const long o = RB * N * i;
         const R k2 = R(double(mfreq<N>(wg.y0 + RB * i)) + del[1]);
         if (par) {
-          sm[so] = src[o];
-          const cx<R> w0 = src[NR + o];
+          sm[so] = SPLIT ? src[o] : pre[0][i];
+          const cx<R> w0 = SPLIT ? src[NR + o] : pre[1][i];
           sm[PL + so] = mul_i(k1 * w0);
           sm[2 * PL + so] = mul_i(k2 * w0);
-          sm[3 * PL + so] = src[2 * NR + o];
+          sm[3 * PL + so] = SPLIT ? src[2 * NR + o] : pre[2][i];
         }
         if (anti) {
-          const cx<R> w0 = src[3 * NR + o];
+          const cx<R> w0 = SPLIT ? src[3 * NR + o] : pre[3][i];
           sm[ab * PL + so] = mul_i(k1 * w0);
           sm[(ab + 1) * PL + so] = mul_i(k2 * w0);
-          sm[(ab + 2) * PL + so] = src[4 * NR + o];
+          sm[(ab + 2) * PL + so] = SPLIT ? src[4 * NR + o] : pre[4][i];
         }
       }
+      if (!SPLIT && q + 1 < wg.qe) fetch(q + 1);
       __syncthreads();
       planes_fft<R, N, 1>(sm, SPLIT ? (g == 0 ? 4 : 3) : 7, threadIdx.x);
 #pragma unroll
@@ -748,6 +780,16 @@ __global__ void __launch_bounds__((Fz<R, N>::NTH)) k_fused_O(const cx<R>* buf4, 
     h5[i] = R(0);
     H[i][0] = H[i][1] = H[i][2] = mk<R>(R(0), R(0));
   }
+  // the next partner's four pair planes are loaded into registers while this partner is transformed
+  cx<R> pre[4][KP];
+  auto fetch = [&](int q) {
+    const cx<R>* src = buf4 + (long(wg.t) * fa.P + q) * 4 * NR + wg.zo;
+#pragma unroll
+    for (int f = 0; f < 4; ++f)
+#pragma unroll
+      for (int i = 0; i < KP; ++i) pre[f][i] = src[f * NR + RB * N * i];
+  };
+  if (!SPLIT && wg.qb < wg.qe) fetch(wg.qb);
   for (int q = wg.qb; q < wg.qe; ++q) {
     const R wq = R(w[q]);
     const long pair = long(wg.t) * fa.P + q;
@@ -764,18 +806,19 @@ __global__ void __launch_bounds__((Fz<R, N>::NTH)) k_fused_O(const cx<R>* buf4, 
         const long o = RB * N * i;
         const R k2 = R(double(mfreq<N>(wg.y0 + RB * i)) + del[1]);
         if (par) {
-          const cx<R> w0 = src[o];
+          const cx<R> w0 = SPLIT ? src[o] : pre[0][i];
           sm[so] = mul_i(k1 * w0);
           sm[PL + so] = mul_i(k2 * w0);
-          sm[2 * PL + so] = src[NR + o];
+          sm[2 * PL + so] = SPLIT ? src[NR + o] : pre[1][i];
         }
         if (anti) {
-          const cx<R> w0 = src[2 * NR + o];
+          const cx<R> w0 = SPLIT ? src[2 * NR + o] : pre[2][i];
           sm[ab * PL + so] = mul_i(k1 * w0);
           sm[(ab + 1) * PL + so] = mul_i(k2 * w0);
-          sm[(ab + 2) * PL + so] = src[3 * NR + o];
+          sm[(ab + 2) * PL + so] = SPLIT ? src[3 * NR + o] : pre[3][i];
         }
       }
+      if (!SPLIT && q + 1 < wg.qe) fetch(q + 1);
       __syncthreads();
       planes_fft<R, N, 1>(sm, SPLIT ? 3 : 6, threadIdx.x);
 #pragma unroll
