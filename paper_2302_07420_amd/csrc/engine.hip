@@ -568,6 +568,8 @@ struct EngineT : Engine {
   // working-precision fields
   DBuf<cx<R>> psi;     // [P][NR]
   DBuf<cx<R>> D;       // [3][P][NR]
+  DBuf<cx<R>> Dl;      // [3][P][NR]  lattice components B D
+  DBuf<cx<R>> Hl;      // [P][3][NR]  lattice components B H3a4
   DBuf<cx<R>> nJ;      // [4][NR]  n, J_x, J_y, J_z
   DBuf<cx<R>> loc;     // [8][NR]  VH, h1 x3, P2bh2, F3b1, h6, F3b2
   DBuf<cx<R>> wk;      // [9][NR]  scratch volumes
@@ -575,7 +577,7 @@ struct EngineT : Engine {
   DBuf<R> h5;          // [P][NR]
   DBuf<cx<R>> bufA;    // [T*P][4][NR]  pair densities, 3b6 and pass-B sources
   DBuf<cx<R>> bufB;    // [T*P][5][NR]  z-stage outputs
-  DBuf<cx<R>> h4, Z;   // [T][3][NR]
+  DBuf<cx<R>> h4, Z;   // [T][3][NR]  h4 (Cartesian), pass-B target factor (lattice)
   DBuf<cx<R>> g;       // [T][NR]
   DBuf<cx<double>> acc;     // [4][T][NR]  FP64 accumulation of the operator output, per energy slot
   DBuf<cx<R>> gpart;        // [S][T][3][NR]  partner-chunk partials
@@ -707,6 +709,8 @@ struct EngineT : Engine {
     if (P == P_alloc && pb.batch == batch_alloc) return;
     psi.alloc(size_t(P) * NR);
     D.alloc(size_t(3) * P * NR);
+    Dl.alloc(size_t(3) * P * NR);
+    Hl.alloc(size_t(3) * P * NR);
     nJ.alloc(4 * NR);
     loc.alloc(8 * NR);
     wk.alloc(9 * NR);
@@ -744,6 +748,11 @@ struct EngineT : Engine {
     const MeshInfo mi{pb.n1, pb.n2, pb.n3, nb, P};
     Recip rc;
     for (int i = 0; i < 9; ++i) rc.b[i] = pb.B[i];
+    Basis<R> bm, mm;   // B_dc = (b_d)_c and the metric M = B B^T, working precision
+    for (int i = 0; i < 9; ++i) bm.b[i] = R(pb.B[i]);
+    for (int d = 0; d < 3; ++d)
+      for (int e = 0; e < 3; ++e)
+        mm.b[3 * d + e] = R(pb.B[3 * d] * pb.B[3 * e] + pb.B[3 * d + 1] * pb.B[3 * e + 1] + pb.B[3 * d + 2] * pb.B[3 * e + 2]);
     const Tables tb{tV.p, tU1.p, tU2.p, dfr.p};
     // algorithmic bytes: fields each launch must read or write once (working precision)
     const double fb = double(sizeof(cx<R>)) * NR;
@@ -771,6 +780,10 @@ struct EngineT : Engine {
     });
     fft3d_t<R, N>(psi.p, P, +1, s, pf);
     fft3d_t<R, N>(D.p, 3L * P, +1, s, pf);
+    K(TC_K_OTHER, 6.0 * fb * P, [&] {
+      hipLaunchKernelGGL((k_lattice3<R, N>), dim3(nblk(long(P) * NR)), dim3(256), 0, s, D.p, Dl.p, bm, long(P), NR,
+                         long(P) * NR);
+    });
     TC_HIP(hipEventRecord(ev.e[1], s));
 
     // ---- 1: densities and Hartree-type fields (Algs. 2ah, 3a1, 3b1; 2bh1, 2bh2)
@@ -834,6 +847,10 @@ struct EngineT : Engine {
       fft3d_t<R, N>(wk.p + 3 * NR, 1, +1, s, pf);
       TC_HIP(hipMemcpyAsync(loc.p + 7 * NR, wk.p + 3 * NR, NR * sizeof(cx<R>), hipMemcpyDeviceToDevice, s));
     }
+    K(TC_K_OTHER, 6.0 * fb * P, [&] {
+      hipLaunchKernelGGL((k_lattice3<R, N>), dim3(nblk(long(P) * NR)), dim3(256), 0, s, H3a4.p, Hl.p, bm, long(P),
+                         3 * NR, NR);
+    });
     TC_HIP(hipEventRecord(ev.e[3], s));
 
     // ---- 3/4: target batches (pass A, pass B, local terms, r -> G)
@@ -863,8 +880,8 @@ struct EngineT : Engine {
                              npair, t0, mi, tb, 1);
         });
         K(TC_K_FUSED_A, fb * ((m.m3b6 ? 9.0 : 5.0) * npair + 8.0 * P + nt) + 6.0 * part, [&] {
-          hipLaunchKernelGGL((k_fused_A<R, N>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, bufB.p, psi.p, D.p,
-                             H3a4.p, nJ.p, sh.w.p, fa, m, int(m.m3b6 != 0), mi, rc, dfr.p, bufA.p, gpart.p,
+          hipLaunchKernelGGL((k_fused_A<R, N>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, bufB.p, psi.p, Dl.p,
+                             Hl.p, nJ.p, sh.w.p, fa, m, int(m.m3b6 != 0), mi, bm, mm, dfr.p, bufA.p, gpart.p,
                              h4part.p);
         });
         K(TC_K_SUM_PARTS, 6.0 * part + 6.0 * fd * nt + 3.0 * fb * nt, [&] {
@@ -891,11 +908,11 @@ struct EngineT : Engine {
         const FusedArgs fy{P, nt, t0, S, chunk};
         K(TC_K_OTHER, fb * 13.0 * nt, [&] {
           hipLaunchKernelGGL((k_passB_Z<R, N>), dim3(nblk(long(nt) * NR)), dim3(256), 0, s, psi.p, D.p, loc.p + NR,
-                             h4.p, t0, nt, P, m, Z.p);
+                             h4.p, t0, nt, P, m, bm, Z.p);
         });
         K(TC_K_XY_PASSB, fb * (2.0 * npair + 4.0 * P + 4.0 * nt), [&] {
-          hipLaunchKernelGGL((k_passB_xy<R, N>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, psi.p, Z.p, H3a4.p, fy,
-                             mi, rc, dfr.p, R(m.m3b5), bufA.p);
+          hipLaunchKernelGGL((k_passB_xy<R, N>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, psi.p, Z.p, Hl.p, fy,
+                             mi, dfr.p, R(m.m3b5), bufA.p);
         });
         K(TC_K_ZCONV_B, fb * 3.0 * npair + tabB, [&] {
           hipLaunchKernelGGL((k_zconv<R, N, OP_B>), dim3(nblk(npair * N * N)), dim3(256), 0, s, bufA.p, bufB.p,

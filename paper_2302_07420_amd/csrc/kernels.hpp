@@ -288,6 +288,30 @@ __device__ __forceinline__ void to_latt(const Basis<R>& B, const cx<R>* S, cx<R>
   for (int d = 0; d < 3; ++d) T[d] = B.b[3 * d] * S[0] + B.b[3 * d + 1] * S[1] + B.b[3 * d + 2] * S[2];
 }
 
+// T_d = sum_e M_de Y_e with the metric M = B B^T (so T = B X for X_c = sum_d B_dc Y_d)
+template <typename R>
+__device__ __forceinline__ void apply_metric(const Basis<R>& M, const cx<R>* Y, cx<R>* T) {
+#pragma unroll
+  for (int d = 0; d < 3; ++d) T[d] = M.b[3 * d] * Y[0] + M.b[3 * d + 1] * Y[1] + M.b[3 * d + 2] * Y[2];
+}
+
+// Lattice components of vector fields: out_d = sum_c B_dc in_c for nvec vectors of N^3 points;
+// component c of vector v at in + v vstride + c cstride (same layout for out).
+template <typename R, int N>
+__global__ void k_lattice3(const cx<R>* in, cx<R>* out, Basis<R> B, long nvec, long vstride, long cstride) {
+  constexpr long NR = long(N) * N * N;
+  const long id = long(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (id >= nvec * NR) return;
+  const long v = id / NR, r = id - v * NR;
+  const long o = v * vstride + r;
+  cx<R> X[3], T[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) X[c] = in[o + c * cstride];
+  to_latt(B, X, T);
+#pragma unroll
+  for (int d = 0; d < 3; ++d) out[o + d * cstride] = T[d];
+}
+
 template <typename R>
 __device__ __forceinline__ void cfma(cx<R>& acc, R a, cx<R> u, cx<R> v) {   // acc += a u v
   const cx<R> p = u * v;
@@ -339,23 +363,44 @@ __device__ __forceinline__ void planes_fft(cx<R>* sm, int np, int tid) {
   __syncthreads();
 }
 
-// common decoding of a plane-kernel work-group
+// Access base[byte offset] with a work-group-uniform base and a 32-bit lane offset, so that the
+// compiler can use the scalar-base + 32-bit vector-offset addressing form.
+template <typename T>
+__device__ __forceinline__ T ldo(const T* base, unsigned byteoff) {
+  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + byteoff);
+}
+template <typename T>
+__device__ __forceinline__ void sto(T* base, unsigned byteoff, T v) {
+  *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + byteoff) = v;
+}
+
+// Logical work-group index from the hardware one.  Work-groups are dealt to the 8 XCDs round-robin;
+// this map gives each XCD a contiguous range of logical indices (bijective for any grid size).
+__device__ __forceinline__ int xcd_major(int b, int n) {
+  const int q8 = n / 8, r8 = n % 8, x = b % 8;
+  return x * q8 + min(x, r8) + b / 8;
+}
+
+// common decoding of a plane-kernel work-group: logical index = (z-plane, chunk) major, target minor,
+// so the work-groups of all targets that read the same partner planes run together on one XCD and
+// share its L2
 template <typename R, int N>
 struct PlaneWG {
   int x, y0, c, z, t, qb, qe;
-  long zo;    // global offset of owned point i: zo + RB N i
-  int so0;    // LDS offset of owned point i: so0 + RB LD i
+  unsigned zo;   // offset of owned point i within a volume: zo + RB N i
+  int so0;       // LDS offset of owned point i: so0 + RB LD i
   __device__ PlaneWG(const FusedArgs& fa) {
     using F = Fz<R, N>;
     const int tid = threadIdx.x;
     x = tid % N;
     y0 = tid / N;
-    c = blockIdx.x % fa.S;
-    z = (blockIdx.x / fa.S) % N;
-    t = blockIdx.x / (fa.S * N);
+    const int L = xcd_major(int(blockIdx.x), int(gridDim.x));
+    t = L % fa.T;
+    c = (L / fa.T) % fa.S;
+    z = L / (fa.T * fa.S);
     qb = c * fa.chunk;
     qe = min(fa.P, qb + fa.chunk);
-    zo = long(z) * N * N + y0 * N + x;
+    zo = unsigned(z * N * N + y0 * N + x);
     so0 = y0 * F::LD + x;
   }
 };
@@ -391,47 +436,51 @@ __global__ void __launch_bounds__((Fz<R, N>::NTH)) k_pair_xy(const cx<R>* psi, F
   }
 }
 
-// Pass-B sources of the pairs (t, q): Y_c = conj(psi_q) Z_tc + m3b5 conj(H3a4_qc) psi_t (TC mode:
-// H3b = conj(H3a4)); Z holds m2bx2 D_j - m3b3 h1 psi_j + m3b4 h4_j.  In lattice components
-// T_d = sum_c B_dc Y_c, forward xy transformed: out[(pair 2 + 0)] = kappa_1 T~_1 + kappa_2 T~_2,
+// Pass-B sources of the pairs (t, q), in lattice components: T_d = conj(psi_q) Zl_td +
+// m3b5 conj(Hl_qd) psi_t, with Zl = B (m2bx2 D_j - m3b3 h1 psi_j + m3b4 h4_j) and Hl = B H3a4 (TC mode:
+// H3b = conj(H3a4)); forward xy transformed: out[(pair 2 + 0)] = kappa_1 T~_1 + kappa_2 T~_2,
 // out[(pair 2 + 1)] = T~_3, pair = t P + q, Delta = k_t - k_q.
-// occupancy target of k_passB_xy: 3 waves per SIMD where that costs no spills (FP32 at 24^3)
+// occupancy target: 3 waves per SIMD where that costs no spills (FP32 at 24^3)
 template <typename R, int N>
 constexpr int kPassBWaves = (sizeof(R) == 4 && N == 24) ? 3 : 1;
 
 template <typename R, int N>
 __global__ void __launch_bounds__((Fz<R, N>::NTH)) __attribute__((amdgpu_waves_per_eu(kPassBWaves<R, N>)))
-k_passB_xy(const cx<R>* psi, const cx<R>* Z, const cx<R>* H3a4,
-                                                            FusedArgs fa, MeshInfo mi, Recip rc, const double* dfr,
-                                                            R m3b5, cx<R>* out) {
+k_passB_xy(const cx<R>* psi, const cx<R>* Zl, const cx<R>* Hl, FusedArgs fa, MeshInfo mi, const double* dfr,
+           R m3b5, cx<R>* out) {
   using F = Fz<R, N>;
   constexpr int KP = F::KP, RB = F::RB;
   constexpr int NPQ = F::GRP / 3 < 1 ? 1 : F::GRP / 3;   // partners per LDS round (three planes each)
   constexpr long NR = long(N) * N * N;
   __shared__ cx<R> sm[3 * NPQ * F::PLANE];
   const PlaneWG<R, N> wg(fa);
-  const Basis<R> B = basis<R>(rc);
   const long jt = fa.t0 + wg.t;
   cx<R> zt[KP][3], pt[KP];
+  {
+    const cx<R>* pj = psi + jt * NR;
+    const cx<R>* zb = Zl + long(wg.t) * 3 * NR;
 #pragma unroll
-  for (int i = 0; i < KP; ++i) {
-    const long r = wg.zo + RB * N * i;
-    pt[i] = psi[jt * NR + r];
+    for (int i = 0; i < KP; ++i) {
+      const unsigned r = wg.zo + RB * N * i;
+      pt[i] = pj[r];
 #pragma unroll
-    for (int cc = 0; cc < 3; ++cc) zt[i][cc] = Z[(long(wg.t) * 3 + cc) * NR + r];
+      for (int d = 0; d < 3; ++d) zt[i][d] = zb[d * NR + r];
+    }
   }
-  // partner fields psi_q, H3a4_q of the next round are loaded while this round is transformed
+  // partner fields psi_q, Hl_q of the next round are loaded while this round is transformed
   cx<R> pre[NPQ][4][KP];
   auto fetch = [&](int q0) {
 #pragma unroll
     for (int a = 0; a < NPQ; ++a) {
       const int q = min(q0 + a, wg.qe - 1);
+      const cx<R>* pq = psi + long(q) * NR;
+      const cx<R>* hq = Hl + long(q) * 3 * NR;
 #pragma unroll
       for (int i = 0; i < KP; ++i) {
-        const long r = wg.zo + RB * N * i;
-        pre[a][0][i] = psi[long(q) * NR + r];
+        const unsigned r = wg.zo + RB * N * i;
+        pre[a][0][i] = pq[r];
 #pragma unroll
-        for (int cc = 0; cc < 3; ++cc) pre[a][1 + cc][i] = H3a4[(long(q) * 3 + cc) * NR + r];
+        for (int d = 0; d < 3; ++d) pre[a][1 + d][i] = hq[d * NR + r];
       }
     }
   };
@@ -443,15 +492,12 @@ k_passB_xy(const cx<R>* psi, const cx<R>* Z, const cx<R>* H3a4,
       if (a >= nq) continue;
 #pragma unroll
       for (int i = 0; i < KP; ++i) {
-        cx<R> Y[3], T[3];
 #pragma unroll
-        for (int cc = 0; cc < 3; ++cc) {
-          Y[cc] = cmulc(pre[a][0][i], zt[i][cc]);
-          if (m3b5 != R(0)) Y[cc] = Y[cc] + m3b5 * cmulc(pre[a][1 + cc][i], pt[i]);
+        for (int d = 0; d < 3; ++d) {
+          cx<R> T = cmulc(pre[a][0][i], zt[i][d]);
+          if (m3b5 != R(0)) T = T + m3b5 * cmulc(pre[a][1 + d][i], pt[i]);
+          sm[(3 * a + d) * F::PLANE + wg.so0 + RB * F::LD * i] = T;
         }
-        to_latt(B, Y, T);
-#pragma unroll
-        for (int d = 0; d < 3; ++d) sm[(3 * a + d) * F::PLANE + wg.so0 + RB * F::LD * i] = T[d];
       }
     }
     if (q0 + NPQ < wg.qe) fetch(q0 + NPQ);
@@ -461,13 +507,14 @@ k_passB_xy(const cx<R>* psi, const cx<R>* Z, const cx<R>* H3a4,
       const int q = q0 + a;
       const double* del = dfr + 3 * pair_dindex(mi, int(jt), q, 1);
       const R k1 = R(double(mfreq<N>(wg.x)) + del[0]);
-      cx<R>* dst = out + (long(wg.t) * fa.P + q) * 2 * NR + wg.zo;
+      cx<R>* dst = out + (long(wg.t) * fa.P + q) * 2 * NR;
 #pragma unroll
       for (int i = 0; i < KP; ++i) {
         const int so = (3 * a) * F::PLANE + wg.so0 + RB * F::LD * i;
+        const unsigned r = wg.zo + RB * N * i;
         const R k2 = R(double(mfreq<N>(wg.y0 + RB * i)) + del[1]);
-        dst[RB * N * i] = k1 * sm[so] + k2 * sm[so + F::PLANE];
-        dst[NR + RB * N * i] = sm[so + 2 * F::PLANE];
+        dst[r] = k1 * sm[so] + k2 * sm[so + F::PLANE];
+        dst[NR + r] = sm[so + 2 * F::PLANE];
       }
     }
     __syncthreads();
@@ -565,14 +612,16 @@ __global__ void __launch_bounds__(256) k_zconv(const cx<R>* in, cx<R>* out, long
 }
 
 // Pass A, fused inverse xy + partner sums.  buf5 per pair (xy in G space):
-// [XV, W0_par, W3_par, W0_anti, W3_anti].  With X^U the Cartesian vector fields, accumulates for the
-// owned points of target t over the chunk's partners q:
-//   slot 0: -m2ax w XV psi_q          (2ax)
-//   slot 1: -m2bx1 w X^U_par . D_q     (2bx1)
-//   slot 2: -m3a4 w H3a4_q . X^U_par   (2 x 3a4)
-//   h4    : w X^U_par psi_q            (h4 of Alg. 3a3)
-// and, if do3b6, writes the 3b6 sources S_s,c = X^U_s,c n in the forward split form
-// src4 per pair [P_par, R_par, P_anti, R_anti].  Delta = k_t - k_q.
+// [XV, W0_par, W3_par, W0_anti, W3_anti]; after the inverse xy transform the lattice components Y_d
+// of the vector fields are in LDS (Cartesian X_c = sum_d B_dc Y_d).  Accumulates for the owned points
+// of target t over the chunk's partners q, with Dl = B D and Hl = B H3a4 (lattice components):
+//   slot 0: -m2ax w XV psi_q                (2ax)
+//   slot 1: -m2bx1 w X_par . D_q = -m2bx1 w Y_par . Dl_q      (2bx1)
+//   slot 2: -m3a4 w H3a4_q . X_par = -m3a4 w Hl_q . Y_par     (2 x 3a4)
+//   h4    : w X_par psi_q  (accumulated as w Y_par psi_q, made Cartesian at the end)   (Alg. 3a3)
+// and, if do3b6, writes the 3b6 sources S_s,c = X_s,c n in the forward split form
+// (lattice T_s = B S_s = n M Y_s, M = B B^T) src4 per pair [P_par, R_par, P_anti, R_anti].
+// Delta = k_t - k_q.
 template <typename R, int N>
 struct PassA {
   static constexpr bool SPLIT = !Fz<R, N>::fits(7);   // spin channels in separate LDS rounds
@@ -580,35 +629,37 @@ struct PassA {
 };
 
 template <typename R, int N>
-__global__ void __launch_bounds__((Fz<R, N>::NTH)) k_fused_A(const cx<R>* buf5, const cx<R>* psi, const cx<R>* D,
-                                                           const cx<R>* H3a4, const cx<R>* n, const double* w,
-                                                           FusedArgs fa, Masks m, int do3b6, MeshInfo mi, Recip rc,
-                                                           const double* dfr, cx<R>* src4, cx<R>* gpart,
-                                                           cx<R>* h4part) {
+__global__ void __launch_bounds__((Fz<R, N>::NTH)) k_fused_A(const cx<R>* buf5, const cx<R>* psi, const cx<R>* Dl,
+                                                           const cx<R>* Hl, const cx<R>* n, const double* w,
+                                                           FusedArgs fa, Masks m, int do3b6, MeshInfo mi,
+                                                           Basis<R> B, Basis<R> M, const double* dfr, cx<R>* src4,
+                                                           cx<R>* gpart, cx<R>* h4part) {
   using F = Fz<R, N>;
   constexpr int KP = F::KP, RB = F::RB, PL = F::PLANE;
   constexpr bool SPLIT = PassA<R, N>::SPLIT;
   constexpr long NR = long(N) * N * N;
   __shared__ cx<R> sm[PassA<R, N>::NPL * PL];
   const PlaneWG<R, N> wg(fa);
-  const Basis<R> B = basis<R>(rc);
   const int jt = fa.t0 + wg.t;
   cx<R> ga[KP][3], h4[KP][3], nk[KP];
+  unsigned ob[KP];   // byte offsets of the owned points within a volume
+#pragma unroll
+  for (int i = 0; i < KP; ++i) ob[i] = (wg.zo + RB * N * i) * unsigned(sizeof(cx<R>));
 #pragma unroll
   for (int i = 0; i < KP; ++i) {
 #pragma unroll
     for (int s = 0; s < 3; ++s) ga[i][s] = h4[i][s] = mk<R>(R(0), R(0));
-    nk[i] = n[wg.zo + RB * N * i];
+    nk[i] = ldo(n, ob[i]);
   }
   const R a0 = R(-m.m2ax), a1 = R(-m.m2bx1), a2 = R(-m.m3a4);
   // the next partner's five pair planes are loaded into registers while this partner is transformed
   cx<R> pre[5][KP];
   auto fetch = [&](int q) {
-    const cx<R>* src = buf5 + (long(wg.t) * fa.P + q) * 5 * NR + wg.zo;
+    const cx<R>* src = buf5 + (long(wg.t) * fa.P + q) * 5 * NR;
 #pragma unroll
     for (int f = 0; f < 5; ++f)
 #pragma unroll
-      for (int i = 0; i < KP; ++i) pre[f][i] = src[f * NR + RB * N * i];
+      for (int i = 0; i < KP; ++i) pre[f][i] = ldo(src + f * NR, ob[i]);
   };
   if (!SPLIT && wg.qb < wg.qe) fetch(wg.qb);
   for (int q = wg.qb; q < wg.qe; ++q) {
@@ -616,7 +667,10 @@ __global__ void __launch_bounds__((Fz<R, N>::NTH)) k_fused_A(const cx<R>* buf5, 
     const long pair = long(wg.t) * fa.P + q;
     const double* del = dfr + 3 * pair_dindex(mi, jt, q, 1);
     const R k1 = R(double(mfreq<N>(wg.x)) + del[0]);
-    const cx<R>* src = buf5 + pair * 5 * NR + wg.zo;
+    const cx<R>* src = buf5 + pair * 5 * NR;
+    const cx<R>* pq = psi + long(q) * NR;
+    const cx<R>* dq = Dl + long(q) * NR;          // component d at dq + d P N^3
+    const cx<R>* hq = Hl + long(q) * 3 * NR;      // component d at hq + d N^3
 #pragma unroll 1
     for (int g = 0; g < (SPLIT ? 2 : 1); ++g) {
       const bool par = !SPLIT || g == 0, anti = !SPLIT || g == 1;
@@ -625,7 +679,7 @@ __global__ void __launch_bounds__((Fz<R, N>::NTH)) k_fused_A(const cx<R>* buf5, 
 #pragma unroll
       for (int i = 0; i < KP; ++i) {
         const int so = wg.so0 + RB * F::LD * i;
-        const long o = RB * N * i;
+        const unsigned o = wg.zo + RB * N * i;
         const R k2 = R(double(mfreq<N>(wg.y0 + RB * i)) + del[1]);
         if (par) {
           sm[so] = SPLIT ? src[o] : pre[0][i];
@@ -646,40 +700,34 @@ __global__ void __launch_bounds__((Fz<R, N>::NTH)) k_fused_A(const cx<R>* buf5, 
       planes_fft<R, N, 1>(sm, SPLIT ? (g == 0 ? 4 : 3) : 7, threadIdx.x);
 #pragma unroll
       for (int i = 0; i < KP; ++i) {
-        const long r = wg.zo + RB * N * i;
+        const unsigned r = wg.zo + RB * N * i;
         const int so = wg.so0 + RB * F::LD * i;
         if (par) {
-          const cx<R> pq = psi[long(q) * NR + r];
-          cfma(ga[i][0], a0 * wq, sm[so], pq);
-          cx<R> Y[3], X[3];
+          const cx<R> p = ldo(pq, ob[i]);
+          cfma(ga[i][0], a0 * wq, sm[so], p);
+          cx<R> Y[3];
 #pragma unroll
           for (int d = 0; d < 3; ++d) Y[d] = sm[(1 + d) * PL + so];
-          to_cart(B, Y, X);
 #pragma unroll
-          for (int cd = 0; cd < 3; ++cd) {
-            cfma(ga[i][1], a1 * wq, X[cd], D[(long(cd) * fa.P + q) * NR + r]);
-            cfma(ga[i][2], a2 * wq, X[cd], H3a4[(long(q) * 3 + cd) * NR + r]);
-            cfma(h4[i][cd], wq, X[cd], pq);
+          for (int d = 0; d < 3; ++d) {
+            cfma(ga[i][1], a1 * wq, Y[d], ldo(dq + long(d) * fa.P * NR, ob[i]));
+            cfma(ga[i][2], a2 * wq, Y[d], ldo(hq + d * NR, ob[i]));
+            cfma(h4[i][d], wq, Y[d], p);
           }
           if (do3b6) {
-            cx<R> S[3], T[3];
+            cx<R> T[3];
+            apply_metric(M, Y, T);
 #pragma unroll
-            for (int cd = 0; cd < 3; ++cd) S[cd] = X[cd] * nk[i];
-            to_latt(B, S, T);
-#pragma unroll
-            for (int d = 0; d < 3; ++d) sm[(1 + d) * PL + so] = T[d];
+            for (int d = 0; d < 3; ++d) sm[(1 + d) * PL + so] = T[d] * nk[i];
           }
         }
         if (anti && do3b6) {
-          cx<R> Y[3], X[3], S[3], T[3];
+          cx<R> Y[3], T[3];
 #pragma unroll
           for (int d = 0; d < 3; ++d) Y[d] = sm[(ab + d) * PL + so];
-          to_cart(B, Y, X);
+          apply_metric(M, Y, T);
 #pragma unroll
-          for (int cd = 0; cd < 3; ++cd) S[cd] = X[cd] * nk[i];
-          to_latt(B, S, T);
-#pragma unroll
-          for (int d = 0; d < 3; ++d) sm[(ab + d) * PL + so] = T[d];
+          for (int d = 0; d < 3; ++d) sm[(ab + d) * PL + so] = T[d] * nk[i];
         }
       }
       __syncthreads();
@@ -687,19 +735,19 @@ __global__ void __launch_bounds__((Fz<R, N>::NTH)) k_fused_A(const cx<R>* buf5, 
         // forward xy of the T planes (slots 1..6 unsplit; 1..3 or 0..2 split), then the split form
         const int s0 = (SPLIT && g == 1) ? 0 : 1;
         planes_fft<R, N, -1>(sm + s0 * PL, SPLIT ? 3 : 6, threadIdx.x);
-        cx<R>* dst = src4 + pair * 4 * NR + wg.zo;
+        cx<R>* dst = src4 + pair * 4 * NR;
 #pragma unroll
         for (int i = 0; i < KP; ++i) {
           const int so = wg.so0 + RB * F::LD * i;
-          const long o = RB * N * i;
+          const unsigned o = wg.zo + RB * N * i;
           const R k2 = R(double(mfreq<N>(wg.y0 + RB * i)) + del[1]);
           if (par) {
-            dst[o] = k1 * sm[PL + so] + k2 * sm[2 * PL + so];
-            dst[NR + o] = sm[3 * PL + so];
+            sto(dst, ob[i], k1 * sm[PL + so] + k2 * sm[2 * PL + so]);
+            sto(dst + NR, ob[i], sm[3 * PL + so]);
           }
           if (anti) {
-            dst[2 * NR + o] = k1 * sm[ab * PL + so] + k2 * sm[(ab + 1) * PL + so];
-            dst[3 * NR + o] = sm[(ab + 2) * PL + so];
+            sto(dst + 2 * NR, ob[i], k1 * sm[ab * PL + so] + k2 * sm[(ab + 1) * PL + so]);
+            sto(dst + 3 * NR, ob[i], sm[(ab + 2) * PL + so]);
           }
         }
         __syncthreads();
@@ -708,11 +756,15 @@ __global__ void __launch_bounds__((Fz<R, N>::NTH)) k_fused_A(const cx<R>* buf5, 
   }
 #pragma unroll
   for (int i = 0; i < KP; ++i) {
-    const long r = wg.zo + RB * N * i;
+    const unsigned r = wg.zo + RB * N * i;
+    cx<R> hc[3];
+    to_cart(B, h4[i], hc);
+    cx<R>* gp = gpart + (long(wg.c) * fa.T + wg.t) * 3 * NR;
+    cx<R>* hp = h4part + (long(wg.c) * fa.T + wg.t) * 3 * NR;
 #pragma unroll
     for (int s = 0; s < 3; ++s) {
-      gpart[((long(wg.c) * fa.T + wg.t) * 3 + s) * NR + r] = ga[i][s];
-      h4part[((long(wg.c) * fa.T + wg.t) * 3 + s) * NR + r] = h4[i][s];
+      sto(gp + s * NR, ob[i], ga[i][s]);
+      sto(hp + s * NR, ob[i], hc[s]);
     }
   }
 }
@@ -1001,10 +1053,10 @@ __global__ void k_reduce_occ(const R* h5, const cx<R>* H3a4, const cx<R>* psi, c
   for (int c = 0; c < 3; ++c) M[c * NR + r] = mk<R>(R(mr[c]), R(mi[c]));
 }
 
-// Z_t = m2bx2 D_j - m3b3 h1 psi_j + m3b4 h4_t  (pass-B target factor)
+// Pass-B target factor in lattice components: Zl_t = B (m2bx2 D_j - m3b3 h1 psi_j + m3b4 h4_t)
 template <typename R, int N>
 __global__ void k_passB_Z(const cx<R>* psi, const cx<R>* D, const cx<R>* h1, const cx<R>* h4, int t0, int T, int P,
-                          Masks m, cx<R>* Z) {
+                          Masks m, Basis<R> B, cx<R>* Zl) {
   constexpr long NR = long(N) * N * N;
   const long id = long(blockIdx.x) * blockDim.x + threadIdx.x;
   if (id >= long(T) * NR) return;
@@ -1012,13 +1064,17 @@ __global__ void k_passB_Z(const cx<R>* psi, const cx<R>* D, const cx<R>* h1, con
   const long r = id - long(t) * NR;
   const long j = t0 + t;
   const cx<R> pj = psi[j * NR + r];
+  cx<R> Zc[3], Zd[3];
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
     cx<R> v = R(m.m2bx2) * D[(long(c) * P + j) * NR + r];
     v = v - R(m.m3b3) * (h1[c * NR + r] * pj);
     v = v + R(m.m3b4) * h4[(long(t) * 3 + c) * NR + r];
-    Z[(long(t) * 3 + c) * NR + r] = v;
+    Zc[c] = v;
   }
+  to_latt(B, Zc, Zd);
+#pragma unroll
+  for (int d = 0; d < 3; ++d) Zl[(long(t) * 3 + d) * NR + r] = Zd[d];
 }
 
 }  // namespace tcmi
