@@ -236,3 +236,52 @@ def from_workload(w, precision=TC_PREC_FP64, terms=TERM_ALL, div_correction=True
     for ik in range(len(w.miller)):
         op.load_orbitals(ik, cs[ik], w.occ[ik])
     return op
+
+
+def energy_function():
+    """torch.autograd.Function for E(c, A, C) of an operator's problem (TC mode).
+
+    ``TCEnergy.apply(op, coeff, A, C, occ)``: ``coeff`` is a complex128 CUDA tensor
+    [nk, nband, npw_max] (rows zero-padded like tc_apply_all), ``A`` and ``C`` float64
+    tensors of shape (2,), ``occ`` a float64 array [nk, nband].  Forward loads the
+    coefficients and Jastrow parameters into ``op`` and returns the energy (float64
+    scalar); backward calls tc_energy_backward_dev, whose gradient convention
+    (dE/dRe c + i dE/dIm c) is the one torch uses for complex leaves.  Only argument
+    marshalling happens here; the energy and its gradient are computed by the library.
+    """
+    import torch
+
+    class TCEnergy(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, op, coeff, A, C, occ):
+            if coeff.dtype != torch.complex128 or not coeff.is_cuda or not coeff.is_contiguous():
+                raise TCError("coeff must be a contiguous complex128 CUDA tensor [nk, nband, npw_max]")
+            nk, nb, npw_max = coeff.shape
+            if npw_max != op.npw_max or nk != len(op.npw):
+                raise TCError("coeff shape does not match the operator's k-mesh and basis")
+            op.set_jastrow(A.detach().cpu().numpy(), C.detach().cpu().numpy())
+            occ = np.asarray(occ, dtype=np.float64).reshape(nk, nb)
+            packed = [coeff[k, :, : op.npw[k]].contiguous() for k in range(nk)]   # [nband][npw(k)] rows
+            torch.cuda.current_stream().synchronize()
+            for k in range(nk):
+                op.load_orbitals_dev(k, packed[k].data_ptr(), nb, occ[k])
+            op.sync()
+            del packed
+            e, _ = op.energy()
+            ctx.op = op
+            ctx.shape = coeff.shape
+            ctx.dev = coeff.device
+            ctx.save_for_backward(coeff)     # kept alive: the library reads it again in backward
+            return torch.tensor(e, dtype=torch.float64)
+
+        @staticmethod
+        def backward(ctx, gE):
+            (coeff,) = ctx.saved_tensors
+            grad = torch.zeros(ctx.shape, dtype=torch.complex128, device=ctx.dev)
+            torch.cuda.current_stream().synchronize()
+            dA, dC = ctx.op.backward_dev(grad.data_ptr())
+            g = float(gE)
+            return (None, grad * g, torch.as_tensor(dA * g, dtype=torch.float64),
+                    torch.as_tensor(dC * g, dtype=torch.float64), None)
+
+    return TCEnergy

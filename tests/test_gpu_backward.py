@@ -140,3 +140,30 @@ def test_backward_error_paths():
     with pytest.raises(tc.TCError, match="status -1"):
         op.backward(want_grad=False, want_params=False)
     op.close()
+
+
+def test_torch_autograd_function():
+    import torch
+
+    w = CASES["fcc_k221_g12"]()
+    E, gc, gA, gC = OG.energy_and_grad(w)
+    _say("[gpu] torch.autograd.Function around the library energy")
+    op = tc.from_workload(w, precision=tc.TC_PREC_FP64)
+    npw_max = op.npw_max
+    c = np.zeros((w.nk, w.right[0].shape[0], npw_max), dtype=np.complex128)
+    for k in range(w.nk):
+        c[k, :, : w.right[k].shape[1]] = w.right[k]
+    coeff = torch.tensor(c, device="cuda", requires_grad=True)
+    A = torch.tensor(w.A, dtype=torch.float64, requires_grad=True)
+    C = torch.tensor(w.C, dtype=torch.float64, requires_grad=True)
+    TCEnergy = tc.energy_function()
+    e = TCEnergy.apply(op, coeff, A, C, np.array(w.occ))
+    e.backward()
+    op.close()
+    assert float(e.detach()) == pytest.approx(E, rel=1e-12)
+    g = coeff.grad.cpu().numpy()
+    scale = max(np.abs(x).max() for x in gc)
+    err = max(np.abs(g[k, :, : gc[k].shape[1]] - gc[k]).max() for k in range(w.nk)) / scale
+    assert err < 1e-10
+    assert np.abs(A.grad.numpy() - gA).max() < 1e-10 * np.abs(gA).max()
+    assert np.abs(C.grad.numpy() - gC).max() < 1e-10 * np.abs(gC).max()
