@@ -141,6 +141,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 GPU path")
+    ap.add_argument("--no-split", action="store_true", help="skip the FP32 + split-BF16 (MFMA z-DFT) path")
     ap.add_argument("--workload", default="fcc_si_k444_g24",
                     help="named workload: fcc_si_k444_g24 (default), heg14_g16, heg54_twist2_g32, fcc_si_x2_k222_g48")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
@@ -176,6 +177,16 @@ def main():
     E32 = e32[-1][0]
     tot, stages = op32.timing()
     log(f"fp32: {ms32:.2f} ms/step (wall {wall32:.2f}), E = {E32:.12f}")
+
+    split = None
+    if not args.no_split:
+        op_s, keep_s = make_op(w, tc.TC_PREC_FP32_SPLITBF16, stream)
+        ms_s, wall_s, e_s, stats_s = time_steps(op_s, out, args.steps, args.warmup, profile=True)
+        split = {"value": w.npairs / (ms_s / 1e3), "ms_per_step": ms_s, "energy_Ha": e_s[-1][0],
+                 "kernels_ms_per_step": {k: v["ms"] / args.steps for k, v in stats_s.items() if v["ms"] > 0}}
+        log(f"fp32+split-bf16: {ms_s:.2f} ms/step, E = {e_s[-1][0]:.12f}")
+        op_s.close()
+        del keep_s
 
     fp64 = None
     if not args.no_fp64:
@@ -237,6 +248,9 @@ def main():
         "energy_rel_err_fp32_vs_fp64": (abs(E32 - fp64["energy_Ha"]) / abs(fp64["energy_Ha"])) if fp64 else None,
         "fp64_gpu": fp64,
         "speedup_fp32_vs_fp64_gpu": (w.npairs / (ms32 / 1e3)) / fp64["value"] if fp64 else None,
+        "fp32_splitbf16_gpu": dict(split, energy_rel_err_vs_fp64=(abs(split["energy_Ha"] - fp64["energy_Ha"])
+                                                                  / abs(fp64["energy_Ha"])) if fp64 else None)
+        if split else None,
         "stages_ms": dict(zip(tc.STAGES, stages)),
         "kernels_ms_per_step": per_kernel,
         "kernel_ms_per_step_total": total_kernel_ms,

@@ -52,7 +52,13 @@ enum {
   TC_ERR_OOM = -7           /* device allocation failed                              */
 };
 
-enum { TC_PREC_FP64 = 0, TC_PREC_FP32 = 1 };
+enum {
+  TC_PREC_FP64 = 0,             /* everything in FP64                                                */
+  TC_PREC_FP32 = 1,             /* FP32 FFT butterflies, pair products and kernel multiplies          */
+  TC_PREC_FP32_SPLITBF16 = 2    /* as FP32, with the DFTs along z as dense GEMMs on the matrix cores in
+                                   split BF16 (hi + lo, three products, FP32 accumulation); grid
+                                   lengths divisible by 8, else TC_ERR_UNSUPPORTED at application   */
+};
 
 /* Term selection bits for tc_set_options (names follow Sec. 2.6 of the paper).
  * Three-body terms enter the operator with multiplicity 2 for 3a3, 3a4 and all
@@ -109,10 +115,10 @@ int tc_set_basis(tc_ctx* ctx, int ik, int npw, const int32_t* miller);
  * the caller's choice (A and C are independent here). */
 int tc_set_jastrow(tc_ctx* ctx, const double A[2], const double C[2]);
 
-/* precision: TC_PREC_FP64 or TC_PREC_FP32 (FFT butterflies, pair products and
- * kernel multiplies in that precision; corrections, overlaps, partner sums and
- * energy reductions always FP64).  alpha: exponent of the auxiliary function
- * exp(-alpha q^2)/q^2 of Eq. aux (bohr^2, > 0).  div_correction: 0/1.
+/* precision: TC_PREC_FP64, TC_PREC_FP32 or TC_PREC_FP32_SPLITBF16 (FFT butterflies,
+ * pair products and kernel multiplies in that precision; corrections, overlaps,
+ * partner sums across chunks and energy reductions always FP64).
+ * alpha: exponent of the auxiliary function exp(-alpha q^2)/q^2 of Eq. aux (bohr^2, > 0).  div_correction: 0/1.
  * term_mask: OR of TC_T_* bits. */
 int tc_set_options(tc_ctx* ctx, int precision, double alpha, int div_correction, uint64_t term_mask);
 

@@ -17,6 +17,7 @@ LIBPATH = os.path.join(HERE, "libtcmi.so")
 
 TC_PREC_FP64 = 0
 TC_PREC_FP32 = 1
+TC_PREC_FP32_SPLITBF16 = 2
 
 TERM_BITS = {
     "2ah": 1 << 0, "2bh1": 1 << 1, "2bh2": 1 << 2, "2ax": 1 << 3, "2bx1": 1 << 4, "2bx2": 1 << 5,

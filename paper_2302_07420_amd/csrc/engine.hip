@@ -18,6 +18,7 @@
 #include <memory>
 #include <string>
 #include <thread>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/tcmi.h"
@@ -704,6 +705,66 @@ struct EngineT : Engine {
     }
   }
 
+  // z stage: register FFTs, or split-BF16 MFMA DFTs (FP32 working precision, N divisible by 8)
+  bool zmfma = false;
+  DBuf<short> zfrag;   // [dir][hi/lo][mt][kt][lane][4] BF16 bits of the real 2N x 2N DFT matrices
+
+  static uint16_t bf16_rne(float f) {
+    uint32_t u;
+    std::memcpy(&u, &f, 4);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return uint16_t(u >> 16);
+  }
+  static float bf16_val(uint16_t h) {
+    const uint32_t u = uint32_t(h) << 16;
+    float f;
+    std::memcpy(&f, &u, 4);
+    return f;
+  }
+
+  void upload_zfrag() {
+    if constexpr (std::is_same<R, float>::value && N % 8 == 0) {
+      constexpr int NT = ZMfma<N>::NT;
+      std::vector<short> f(size_t(ZMfma<N>::NFRAG) * 4);
+      for (int dir = 0; dir < 2; ++dir) {
+        const double sgn = dir == 0 ? -1.0 : 1.0;   // forward e^{-2 pi i z'z/N}, inverse e^{+...}
+        auto M = [&](int row, int col) {
+          const int zp = row / 2, cp = row % 2, z = col / 2, c = col % 2;
+          const double a = sgn * 2.0 * kPi * double((long(zp) * z) % N) / N;
+          const double wr = std::cos(a), wi = std::sin(a);
+          return cp == 0 ? (c == 0 ? wr : -wi) : (c == 0 ? wi : wr);
+        };
+        for (int mt = 0; mt < NT; ++mt)
+          for (int kt = 0; kt < NT; ++kt)
+            for (int l = 0; l < 64; ++l)
+              for (int j = 0; j < 4; ++j) {
+                const double v = M(16 * mt + l % 16, 16 * kt + 4 * (l / 16) + j);
+                const uint16_t hi = bf16_rne(float(v));
+                const uint16_t lo = bf16_rne(float(v - double(bf16_val(hi))));
+                f[size_t(ZMfma<N>::frag(dir, 0, mt, kt) + l) * 4 + j] = short(hi);
+                f[size_t(ZMfma<N>::frag(dir, 1, mt, kt) + l) * 4 + j] = short(lo);
+              }
+      }
+      zfrag.alloc(f.size());
+      TC_HIP(hipMemcpy(zfrag.p, f.data(), f.size() * sizeof(short), hipMemcpyHostToDevice));
+    }
+  }
+
+  template <int OP>
+  void zconv(hipStream_t s, long npair, int t0, const MeshInfo& mi, const Tables& tb, int sign) {
+    if constexpr (std::is_same<R, float>::value && N % 8 == 0) {
+      if (zmfma) {
+        const long groups = npair * (long(N) * N / 16);
+        const unsigned nb = unsigned(std::min<long>((groups + 3) / 4, 8192));
+        hipLaunchKernelGGL((k_zconv_mfma<N, OP>), dim3(nb), dim3(256), 0, s, bufA.p, bufB.p, npair, t0, mi, tb, sign,
+                           reinterpret_cast<const bf16x4*>(zfrag.p));
+        return;
+      }
+    }
+    hipLaunchKernelGGL((k_zconv<R, N, OP>), dim3(nblk(npair * N * N)), dim3(256), 0, s, bufA.p, bufB.p, npair, t0, mi,
+                       tb, sign);
+  }
+
   void ensure(const Problem& pb, size_t budget_bytes) {
     const int P = pb.P();
     if (P == P_alloc && pb.batch == batch_alloc) return;
@@ -824,8 +885,7 @@ struct EngineT : Engine {
                              bufA.p);
         });
         K(TC_K_ZCONV_OCC, fb * 5.0 * npair + tabB, [&] {
-          hipLaunchKernelGGL((k_zconv<R, N, OP_O>), dim3(nblk(npair * N * N)), dim3(256), 0, s, bufA.p, bufB.p,
-                             npair, a0, mi, tb, 0);
+          zconv<OP_O>(s, npair, a0, mi, tb, 0);
         });
         K(TC_K_FUSED_O, fb * (4.0 * npair + P) + 3.5 * fb * nt * S, [&] {
           hipLaunchKernelGGL((k_fused_O<R, N>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, bufB.p, psi.p, sh.w.p,
@@ -876,8 +936,7 @@ struct EngineT : Engine {
                              bufA.p);
         });
         K(TC_K_ZCONV_A1, fb * 6.0 * npair + tabB, [&] {
-          hipLaunchKernelGGL((k_zconv<R, N, OP_A1>), dim3(nblk(npair * N * N)), dim3(256), 0, s, bufA.p, bufB.p,
-                             npair, t0, mi, tb, 1);
+          zconv<OP_A1>(s, npair, t0, mi, tb, 1);
         });
         K(TC_K_FUSED_A, fb * ((m.m3b6 ? 9.0 : 5.0) * npair + 8.0 * P + nt) + 6.0 * part, [&] {
           hipLaunchKernelGGL((k_fused_A<R, N>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, bufB.p, psi.p, Dl.p,
@@ -890,8 +949,7 @@ struct EngineT : Engine {
         });
         if (m.m3b6) {
           K(TC_K_ZCONV_A2, fb * 5.0 * npair + tabB, [&] {
-            hipLaunchKernelGGL((k_zconv<R, N, OP_A2>), dim3(nblk(npair * N * N)), dim3(256), 0, s, bufA.p, bufB.p,
-                               npair, t0, mi, tb, 1);
+            zconv<OP_A2>(s, npair, t0, mi, tb, 1);
           });
           K(TC_K_FUSED_Y, fb * (npair + P) + part, [&] {
             hipLaunchKernelGGL((k_fused_Y<R, N>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, bufB.p, psi.p,
@@ -915,8 +973,7 @@ struct EngineT : Engine {
                              mi, dfr.p, R(m.m3b5), bufA.p);
         });
         K(TC_K_ZCONV_B, fb * 3.0 * npair + tabB, [&] {
-          hipLaunchKernelGGL((k_zconv<R, N, OP_B>), dim3(nblk(npair * N * N)), dim3(256), 0, s, bufA.p, bufB.p,
-                             npair, t0, mi, tb, 1);
+          zconv<OP_B>(s, npair, t0, mi, tb, 1);
         });
         K(TC_K_FUSED_Y, fb * (npair + P) + part, [&] {
           hipLaunchKernelGGL((k_fused_Y<R, N>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, bufB.p, psi.p, sh.w.p,
@@ -1029,15 +1086,23 @@ struct EngineT : Engine {
   }
 };
 
+template <typename R, int N>
+Engine* new_engine(bool zmfma) {
+  auto* e = new EngineT<R, N>();
+  e->zmfma = zmfma;
+  if (zmfma) e->upload_zfrag();
+  return e;
+}
+
 template <typename R>
-Engine* make_engine_r(int N) {
+Engine* make_engine_r(int N, bool zmfma = false) {
   switch (N) {
-    case 8: return new EngineT<R, 8>();
-    case 12: return new EngineT<R, 12>();
-    case 16: return new EngineT<R, 16>();
-    case 24: return new EngineT<R, 24>();
-    case 32: return new EngineT<R, 32>();
-    case 48: return new EngineT<R, 48>();
+    case 8: return new_engine<R, 8>(zmfma);
+    case 12: return new_engine<R, 12>(zmfma);
+    case 16: return new_engine<R, 16>(zmfma);
+    case 24: return new_engine<R, 24>(zmfma);
+    case 32: return new_engine<R, 32>(zmfma);
+    case 48: return new_engine<R, 48>(zmfma);
     default: return nullptr;
   }
 }
@@ -1118,7 +1183,10 @@ int prepare(tc_ctx* c) {
   for (int k = 0; k < pb.nk; ++k)
     if (!pb.loaded[k]) return fail(c, TC_ERR_STATE, "orbitals of k-point " + std::to_string(k) + " not loaded");
   if (!c->eng || c->eng_prec != pb.prec || c->eng_N != pb.N) {
-    c->eng.reset(pb.prec == TC_PREC_FP64 ? make_engine_r<double>(pb.N) : make_engine_r<float>(pb.N));
+    if (pb.prec == TC_PREC_FP32_SPLITBF16 && pb.N % 8 != 0)
+      return fail(c, TC_ERR_UNSUPPORTED, "split-BF16 DFT stages need a grid length divisible by 8");
+    c->eng.reset(pb.prec == TC_PREC_FP64 ? make_engine_r<double>(pb.N)
+                                         : make_engine_r<float>(pb.N, pb.prec == TC_PREC_FP32_SPLITBF16));
     if (!c->eng) return fail(c, TC_ERR_UNSUPPORTED, "grid not supported");
     c->eng_prec = pb.prec;
     c->eng_N = pb.N;
@@ -1452,7 +1520,8 @@ int tc_set_jastrow(tc_ctx* c, const double A[2], const double C[2]) {
 
 int tc_set_options(tc_ctx* c, int precision, double alpha, int div_correction, uint64_t term_mask) {
   return guard(c, [&]() -> int {
-    if (precision != TC_PREC_FP64 && precision != TC_PREC_FP32) return fail(c, TC_ERR_ARG, "unknown precision");
+    if (precision != TC_PREC_FP64 && precision != TC_PREC_FP32 && precision != TC_PREC_FP32_SPLITBF16)
+      return fail(c, TC_ERR_ARG, "unknown precision");
     if (!(alpha > 0.0)) return fail(c, TC_ERR_ARG, "alpha must be > 0");
     Problem& pb = c->pb;
     pb.prec = precision;

@@ -12,6 +12,7 @@
 // physical convolution sum_G K(Delta+G) FT[source_phys](G) e^{iG.r}.
 #pragma once
 #include "fft_reg.hpp"
+#include <hip/hip_bf16.h>
 
 namespace tcmi {
 
@@ -608,6 +609,205 @@ __global__ void __launch_bounds__(256) k_zconv(const cx<R>* in, cx<R>* out, long
     cx<R>* o = out + pair * NR + xy;
 #pragma unroll
     for (int z = 0; z < N; ++z) o[z * NN] = acc[z];
+  }
+}
+
+// ---------------------------------------------------------------- z stage on the matrix cores
+// Split-BF16 variant of k_zconv (working precision FP32): every length-N DFT along z is a dense real
+// GEMM on v_mfma_f32_16x16x16_bf16.  A column of N complex values is a real vector of 2N rows with
+// real and imaginary parts interleaved (row 2z + c), so the DFT is the 2N x 2N real matrix with 2x2
+// blocks [[w_r, -w_i], [w_i, w_r]], w = e^{DIR 2 pi i z' z / N}, cut into NT x NT tiles of 16 x 16
+// (NT = N/8).  A wave owns 16 columns.  Operand lane layouts (16x16x16): A lane l holds
+// A[l%16][4(l/16) + j], B lane l holds B[4(l/16) + j][l%16], D lane l holds D[4(l/16) + v][l%16],
+// j, v = 0..3; with interleaved rows a lane therefore holds two consecutive complex values
+// (z = 8 tile + 2(l/16) + {0, 1}) of its column in A-, B- and D-form alike, and a DFT's result feeds
+// the next DFT as its B operand unchanged.  Each operand x is split x = hi + lo in BF16
+// (round-to-nearest-even, lo = bf16(x - hi)) and a product is hi_A hi_B + hi_A lo_B + lo_A hi_B,
+// accumulated in FP32.  The matrix fragments (both directions, hi and lo) come from the host in lane
+// order and are staged in LDS.
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+template <int N>
+struct ZMfma {
+  static constexpr int NT = N / 8;                     // 16-row tiles of 2N interleaved rows
+  static constexpr int NFRAG = 2 * 2 * NT * NT * 64;   // [dir][hi/lo][mt][kt][lane]
+  static constexpr int frag(int dir, int hl, int mt, int kt) { return (((dir * 2 + hl) * NT + mt) * NT + kt) * 64; }
+};
+
+__device__ __forceinline__ unsigned bf16x2_rne(float a, float b) {
+  __hip_bfloat162 p = __float22bfloat162_rn(make_float2(a, b));
+  return *reinterpret_cast<unsigned*>(&p);     // low half a, high half b
+}
+
+// x (4 FP32 rows of one lane) -> hi, lo in BF16
+__device__ __forceinline__ void split_bf16(const f32x4& x, bf16x4& hi, bf16x4& lo) {
+  const unsigned h0 = bf16x2_rne(x.x, x.y), h1 = bf16x2_rne(x.z, x.w);
+  const float r0 = x.x - __uint_as_float(h0 << 16), r1 = x.y - __uint_as_float(h0 & 0xffff0000u);
+  const float r2 = x.z - __uint_as_float(h1 << 16), r3 = x.w - __uint_as_float(h1 & 0xffff0000u);
+  const unsigned l0 = bf16x2_rne(r0, r1), l1 = bf16x2_rne(r2, r3);
+  uint2 uh{h0, h1}, ul{l0, l1};
+  hi = *reinterpret_cast<bf16x4*>(&uh);
+  lo = *reinterpret_cast<bf16x4*>(&ul);
+}
+
+// Y[mt] = sum_kt F_dir[mt][kt] X[kt] (split-BF16 products, FP32 accumulation)
+template <int N>
+__device__ __forceinline__ void dft_mfma(const bf16x4* frag, int dir, int lane, const f32x4* X, f32x4* Y) {
+  constexpr int NT = ZMfma<N>::NT;
+  bf16x4 xh[NT], xl[NT];
+#pragma unroll
+  for (int kt = 0; kt < NT; ++kt) split_bf16(X[kt], xh[kt], xl[kt]);
+  // the NT output tiles are independent accumulation chains: interleave them to hide MFMA latency
+#pragma unroll
+  for (int mt = 0; mt < NT; ++mt) Y[mt] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int kt = 0; kt < NT; ++kt) {
+#pragma unroll
+    for (int mt = 0; mt < NT; ++mt)
+      Y[mt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(frag[ZMfma<N>::frag(dir, 0, mt, kt) + lane], xh[kt], Y[mt],
+                                                       0, 0, 0);
+#pragma unroll
+    for (int mt = 0; mt < NT; ++mt)
+      Y[mt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(frag[ZMfma<N>::frag(dir, 0, mt, kt) + lane], xl[kt], Y[mt],
+                                                       0, 0, 0);
+#pragma unroll
+    for (int mt = 0; mt < NT; ++mt)
+      Y[mt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(frag[ZMfma<N>::frag(dir, 1, mt, kt) + lane], xh[kt], Y[mt],
+                                                       0, 0, 0);
+  }
+}
+
+// complex helpers on the two values (z0, z0 + 1) a lane holds in one tile: (x, y) and (z, w)
+__device__ __forceinline__ f32x4 cscale(const f32x4& v, float a, float b) {   // (a v0, b v1)
+  return f32x4{a * v.x, a * v.y, b * v.z, b * v.w};
+}
+__device__ __forceinline__ f32x4 imul_scale(const f32x4& v, float a, float b) {   // (i a v0, i b v1)
+  return f32x4{-a * v.y, a * v.x, -b * v.w, b * v.z};
+}
+
+template <int N, int OP>
+__global__ void __launch_bounds__(256) k_zconv_mfma(const cx<float>* in, cx<float>* out, long npairs, int t0,
+                                                    MeshInfo mi, Tables tb, int sign_target_minus_partner,
+                                                    const bf16x4* frag_g) {
+  using Z = ZMfma<N>;
+  constexpr int NT = Z::NT, NN = N * N, GPP = NN / 16;   // column groups per pair
+  constexpr long NR = long(N) * N * N;
+  constexpr int NIN = OpShape<OP>::nin, NOUT = OpShape<OP>::nout;
+  __shared__ bf16x4 frag[Z::NFRAG];
+  for (int e = threadIdx.x; e < Z::NFRAG; e += blockDim.x) frag[e] = frag_g[e];
+  __syncthreads();
+  const int lane = threadIdx.x % 64, wave = threadIdx.x / 64, g4 = lane / 16, jc = lane % 16;
+  const long ngroups = npairs * GPP;
+  const long stride = long(gridDim.x) * 4;
+  // lane's z values in tile m: z0 = 8 m + 2 g4 and z0 + 1
+  auto load_col = [&](const cx<float>* b, f32x4* X) {
+#pragma unroll
+    for (int m = 0; m < NT; ++m) {
+      const int z0 = 8 * m + 2 * g4;
+      const cx<float> a = b[z0 * NN], c = b[(z0 + 1) * NN];
+      X[m] = f32x4{a.x, a.y, c.x, c.y};
+    }
+  };
+  auto store_col = [&](cx<float>* b, const f32x4* Yv) {
+#pragma unroll
+    for (int m = 0; m < NT; ++m) {
+      const int z0 = 8 * m + 2 * g4;
+      b[z0 * NN] = mk<float>(Yv[m].x, Yv[m].y);
+      b[(z0 + 1) * NN] = mk<float>(Yv[m].z, Yv[m].w);
+    }
+  };
+  auto col_base = [&](long grp, long& pair, int& xy) {
+    pair = grp / GPP;
+    xy = int(grp - pair * GPP) * 16 + jc;
+  };
+  // inputs of the next column group are loaded while this one is transformed
+  f32x4 pre[NIN][NT];
+  auto fetch = [&](long grp) {
+    long pair;
+    int xy;
+    col_base(grp, pair, xy);
+#pragma unroll
+    for (int c = 0; c < NIN; ++c) load_col(in + (pair * NIN + c) * NR + xy, pre[c]);
+  };
+  long grp = long(blockIdx.x) * 4 + wave;
+  if (grp < ngroups) fetch(grp);
+  for (; grp < ngroups; grp += stride) {
+    long pair;
+    int xy;
+    col_base(grp, pair, xy);
+    f32x4 X[NIN][NT];
+#pragma unroll
+    for (int c = 0; c < NIN; ++c)
+#pragma unroll
+      for (int m = 0; m < NT; ++m) X[c][m] = pre[c][m];
+    if (grp + stride < ngroups) fetch(grp + stride);
+    const int t = int(pair / mi.P), q = int(pair - long(t) * mi.P);
+    const int di = pair_dindex(mi, t0 + t, q, sign_target_minus_partner);
+    const float* tV = reinterpret_cast<const float*>(tb.V) + long(di) * NR + xy;
+    const float* tU[2] = {reinterpret_cast<const float*>(tb.U1) + long(di) * NR + xy,
+                          reinterpret_cast<const float*>(tb.U2) + long(di) * NR + xy};
+    const float d3 = float(tb.dfr[3 * di + 2]);
+    auto kap3 = [&](int z) { return float(mfreq<N>(z)) + d3; };
+    f32x4 Y[NT], V[NT], O[NT];
+    if constexpr (NIN == 1) {
+      dft_mfma<N>(frag, 0, lane, X[0], Y);
+      cx<float>* ob = out + pair * NOUT * NR + xy;
+      if constexpr (OP == OP_A1) {
+#pragma unroll
+        for (int m = 0; m < NT; ++m) {
+          const int z0 = 8 * m + 2 * g4;
+          V[m] = cscale(Y[m], tV[z0 * NN], tV[(z0 + 1) * NN]);
+        }
+        dft_mfma<N>(frag, 1, lane, V, O);
+        store_col(ob, O);
+        ob += NR;
+      }
+#pragma unroll 1
+      for (int s = 0; s < 2; ++s) {
+        float u0[NT], u1[NT];
+#pragma unroll
+        for (int m = 0; m < NT; ++m) {
+          const int z0 = 8 * m + 2 * g4;
+          u0[m] = tU[s][z0 * NN];
+          u1[m] = tU[s][(z0 + 1) * NN];
+          V[m] = cscale(Y[m], u0[m], u1[m]);
+        }
+        dft_mfma<N>(frag, 1, lane, V, O);
+        store_col(ob, O);
+#pragma unroll
+        for (int m = 0; m < NT; ++m) {
+          const int z0 = 8 * m + 2 * g4;
+          V[m] = imul_scale(Y[m], kap3(z0) * u0[m], kap3(z0 + 1) * u1[m]);
+        }
+        dft_mfma<N>(frag, 1, lane, V, O);
+        store_col(ob + NR, O);
+        ob += 2 * NR;
+      }
+    } else {
+#pragma unroll
+      for (int m = 0; m < NT; ++m) V[m] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int s = 0; s < NIN / 2; ++s) {
+        dft_mfma<N>(frag, 0, lane, X[2 * s], Y);
+#pragma unroll
+        for (int m = 0; m < NT; ++m) {
+          const int z0 = 8 * m + 2 * g4;
+          V[m] += cscale(Y[m], tU[s][z0 * NN], tU[s][(z0 + 1) * NN]);
+        }
+        dft_mfma<N>(frag, 0, lane, X[2 * s + 1], Y);
+#pragma unroll
+        for (int m = 0; m < NT; ++m) {
+          const int z0 = 8 * m + 2 * g4;
+          V[m] += cscale(Y[m], kap3(z0) * tU[s][z0 * NN], kap3(z0 + 1) * tU[s][(z0 + 1) * NN]);
+        }
+      }
+      // OP_A2: -i acc; OP_B: +i acc
+#pragma unroll
+      for (int m = 0; m < NT; ++m) V[m] = OP == OP_A2 ? imul_scale(V[m], -1.f, -1.f) : imul_scale(V[m], 1.f, 1.f);
+      dft_mfma<N>(frag, 1, lane, V, O);
+      store_col(out + pair * NR + xy, O);
+    }
   }
 }
 
