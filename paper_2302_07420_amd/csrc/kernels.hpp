@@ -651,9 +651,16 @@ __device__ __forceinline__ void split_bf16(const f32x4& x, bf16x4& hi, bf16x4& l
   lo = *reinterpret_cast<bf16x4*>(&ul);
 }
 
+// A fragment of the DFT matrix, read through an LDS (address space 3) pointer so that it is a ds_read
+typedef const __attribute__((address_space(3))) bf16x4* lds_frag_ptr;
+template <int N>
+__device__ __forceinline__ bf16x4 frag_at(lds_frag_ptr frag, int idx) {
+  return frag[idx];
+}
+
 // Y[mt] = sum_kt F_dir[mt][kt] X[kt] (split-BF16 products, FP32 accumulation)
 template <int N>
-__device__ __forceinline__ void dft_mfma(const bf16x4* frag, int dir, int lane, const f32x4* X, f32x4* Y) {
+__device__ __forceinline__ void dft_mfma(lds_frag_ptr frag, int dir, int lane, const f32x4* X, f32x4* Y) {
   constexpr int NT = ZMfma<N>::NT;
   bf16x4 xh[NT], xl[NT];
 #pragma unroll
@@ -663,18 +670,21 @@ __device__ __forceinline__ void dft_mfma(const bf16x4* frag, int dir, int lane, 
   for (int mt = 0; mt < NT; ++mt) Y[mt] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
   for (int kt = 0; kt < NT; ++kt) {
+    // beyond 4 x 4 tiles, keep the fragments of this stage out of registers across stages and
+    // group iterations (a compiler-only fence: no instruction, nothing is loaded by it)
+    if constexpr (NT > 4) asm volatile("" ::: "memory");
 #pragma unroll
     for (int mt = 0; mt < NT; ++mt)
-      Y[mt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(frag[ZMfma<N>::frag(dir, 0, mt, kt) + lane], xh[kt], Y[mt],
-                                                       0, 0, 0);
+      Y[mt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(frag_at<N>(frag, ZMfma<N>::frag(dir, 0, mt, kt) + lane),
+                                                       xh[kt], Y[mt], 0, 0, 0);
 #pragma unroll
     for (int mt = 0; mt < NT; ++mt)
-      Y[mt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(frag[ZMfma<N>::frag(dir, 0, mt, kt) + lane], xl[kt], Y[mt],
-                                                       0, 0, 0);
+      Y[mt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(frag_at<N>(frag, ZMfma<N>::frag(dir, 0, mt, kt) + lane),
+                                                       xl[kt], Y[mt], 0, 0, 0);
 #pragma unroll
     for (int mt = 0; mt < NT; ++mt)
-      Y[mt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(frag[ZMfma<N>::frag(dir, 1, mt, kt) + lane], xh[kt], Y[mt],
-                                                       0, 0, 0);
+      Y[mt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(frag_at<N>(frag, ZMfma<N>::frag(dir, 1, mt, kt) + lane),
+                                                       xh[kt], Y[mt], 0, 0, 0);
   }
 }
 
@@ -694,9 +704,12 @@ __global__ void __launch_bounds__(256) k_zconv_mfma(const cx<float>* in, cx<floa
   constexpr int NT = Z::NT, NN = N * N, GPP = NN / 16;   // column groups per pair
   constexpr long NR = long(N) * N * N;
   constexpr int NIN = OpShape<OP>::nin, NOUT = OpShape<OP>::nout;
-  __shared__ bf16x4 frag[Z::NFRAG];
-  for (int e = threadIdx.x; e < Z::NFRAG; e += blockDim.x) frag[e] = frag_g[e];
+  __shared__ bf16x4 frag_sm[Z::NFRAG];
+  for (int e = threadIdx.x; e < Z::NFRAG; e += blockDim.x) frag_sm[e] = frag_g[e];
   __syncthreads();
+  const lds_frag_ptr frag = (lds_frag_ptr)(frag_sm);
+  // register budget: the next group's inputs are prefetched only up to 4 x 4 tiles
+  constexpr bool kPrefetch = NT <= 4;
   const int lane = threadIdx.x % 64, wave = threadIdx.x / 64, g4 = lane / 16, jc = lane % 16;
   const long ngroups = npairs * GPP;
   const long stride = long(gridDim.x) * 4;
@@ -731,17 +744,13 @@ __global__ void __launch_bounds__(256) k_zconv_mfma(const cx<float>* in, cx<floa
     for (int c = 0; c < NIN; ++c) load_col(in + (pair * NIN + c) * NR + xy, pre[c]);
   };
   long grp = long(blockIdx.x) * 4 + wave;
-  if (grp < ngroups) fetch(grp);
+  if (kPrefetch && grp < ngroups) fetch(grp);
   for (; grp < ngroups; grp += stride) {
     long pair;
     int xy;
     col_base(grp, pair, xy);
-    f32x4 X[NIN][NT];
-#pragma unroll
-    for (int c = 0; c < NIN; ++c)
-#pragma unroll
-      for (int m = 0; m < NT; ++m) X[c][m] = pre[c][m];
-    if (grp + stride < ngroups) fetch(grp + stride);
+    if (!kPrefetch) fetch(grp);
+    const bool more = kPrefetch && grp + stride < ngroups;
     const int t = int(pair / mi.P), q = int(pair - long(t) * mi.P);
     const int di = pair_dindex(mi, t0 + t, q, sign_target_minus_partner);
     const float* tV = reinterpret_cast<const float*>(tb.V) + long(di) * NR + xy;
@@ -751,7 +760,8 @@ __global__ void __launch_bounds__(256) k_zconv_mfma(const cx<float>* in, cx<floa
     auto kap3 = [&](int z) { return float(mfreq<N>(z)) + d3; };
     f32x4 Y[NT], V[NT], O[NT];
     if constexpr (NIN == 1) {
-      dft_mfma<N>(frag, 0, lane, X[0], Y);
+      dft_mfma<N>(frag, 0, lane, pre[0], Y);
+      if (more) fetch(grp + stride);   // the inputs are consumed: load the next group's
       cx<float>* ob = out + pair * NOUT * NR + xy;
       if constexpr (OP == OP_A1) {
 #pragma unroll
@@ -789,19 +799,20 @@ __global__ void __launch_bounds__(256) k_zconv_mfma(const cx<float>* in, cx<floa
       for (int m = 0; m < NT; ++m) V[m] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (int s = 0; s < NIN / 2; ++s) {
-        dft_mfma<N>(frag, 0, lane, X[2 * s], Y);
+        dft_mfma<N>(frag, 0, lane, pre[2 * s], Y);
 #pragma unroll
         for (int m = 0; m < NT; ++m) {
           const int z0 = 8 * m + 2 * g4;
           V[m] += cscale(Y[m], tU[s][z0 * NN], tU[s][(z0 + 1) * NN]);
         }
-        dft_mfma<N>(frag, 0, lane, X[2 * s + 1], Y);
+        dft_mfma<N>(frag, 0, lane, pre[2 * s + 1], Y);
 #pragma unroll
         for (int m = 0; m < NT; ++m) {
           const int z0 = 8 * m + 2 * g4;
           V[m] += cscale(Y[m], kap3(z0) * tU[s][z0 * NN], kap3(z0 + 1) * tU[s][(z0 + 1) * NN]);
         }
       }
+      if (more) fetch(grp + stride);   // the inputs are consumed: load the next group's
       // OP_A2: -i acc; OP_B: +i acc
 #pragma unroll
       for (int m = 0; m < NT; ++m) V[m] = OP == OP_A2 ? imul_scale(V[m], -1.f, -1.f) : imul_scale(V[m], 1.f, 1.f);

@@ -31,7 +31,7 @@ def _rel(a, b):
     return max(np.abs(x - y).max() for x, y in zip(a, b)) / scale
 
 
-@pytest.mark.parametrize("grid,kmesh,nb", [(8, (2, 1, 1), 2), (16, (1, 2, 1), 2)])
+@pytest.mark.parametrize("grid,kmesh,nb", [(8, (2, 1, 1), 2), (16, (1, 2, 1), 2), (48, (2, 1, 1), 2)])
 def test_small_cases_vs_oracle(grid, kmesh, nb):
     w = T.tiny_fcc(kmesh=kmesh, grid=grid, ecut=2.0 if grid == 8 else 3.0, nb=nb, a=6.0 if grid == 8 else 7.0,
                    occ=[1.0, 0.7][:nb])
@@ -77,6 +77,22 @@ def test_bench_workload_vs_fp64():
     _say(f"[gpu] split-bf16 fcc_si_k444_g24: element error {err:.3e}, energy error {eerr:.3e}")
     assert err < ELEM_TOL
     assert eerr < ENERGY_TOL
+
+
+def test_supercell_48_vs_fp32_repeatable():
+    """48^3 (six 16-row tiles per DFT): every element finite, close to FP32, identical on a second run."""
+    w = T.workload("fcc_si_x2_k222_g48")
+    out = {}
+    for name, prec in (("fp32", tc.TC_PREC_FP32), ("split", tc.TC_PREC_FP32_SPLITBF16), ("split2", tc.TC_PREC_FP32_SPLITBF16)):
+        op = tc.from_workload(w, precision=prec)
+        out[name] = (op.apply(), op.energy()[0])
+        op.close()
+    assert all(np.isfinite(x).all() for x in out["split"][0])
+    err = _rel(out["split"][0], out["fp32"][0])
+    _say(f"[gpu] split-bf16 supercell 48^3: element difference to FP32 {err:.3e}")
+    assert err < ELEM_TOL
+    assert all(np.array_equal(a, b) for a, b in zip(out["split"][0], out["split2"][0]))
+    assert abs(out["split"][1] - out["fp32"][1]) < ENERGY_TOL * abs(out["fp32"][1])
 
 
 def test_grid_not_divisible_by_8_is_rejected():
