@@ -77,6 +77,24 @@ def make_op(w, precision, stream):
     return op, keep
 
 
+def make_op_bitc(w, precision, stream):
+    """Same problem shape in the biorthogonal mode (left orbitals loaded from the host; the library
+    biorthogonalises them on the device before the timed region)."""
+    import paper_2302_07420_amd as tc
+
+    op = tc.TCOperator(0, stream)
+    op.set_cell(w.lattice)
+    op.set_kmesh(*w.kmesh)
+    op.set_grid(*w.grid)
+    for ik, m in enumerate(w.miller):
+        op.set_basis(ik, m)
+    op.set_jastrow(w.A, w.C)
+    op.set_options(precision, w.alpha, True, tc.TERM_ALL)
+    for ik in range(w.nk):
+        op.load_orbitals(ik, w.right[ik], w.occ[ik], left=w.left[ik])
+    return op
+
+
 def time_steps(op, out, steps, warmup, profile=False):
     import torch
 
@@ -142,6 +160,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 GPU path")
     ap.add_argument("--no-split", action="store_true", help="skip the FP32 + split-BF16 (MFMA z-DFT) path")
+    ap.add_argument("--no-bitc", action="store_true", help="skip the biorthogonal-mode side measurement")
     ap.add_argument("--workload", default="fcc_si_k444_g24",
                     help="named workload: fcc_si_k444_g24 (default), heg14_g16, heg54_twist2_g32, fcc_si_x2_k222_g48")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
@@ -198,6 +217,22 @@ def main():
         op64.close()
         del keep64
 
+    bitc = None
+    if not args.no_bitc and args.workload == "fcc_si_k444_g24":
+        wb = T.workload("fcc_si_k444_g24_bitc")
+        res_b = {}
+        for name, prec, nst in (("fp32", tc.TC_PREC_FP32, args.steps), ("fp64", tc.TC_PREC_FP64, 1)):
+            op_b = make_op_bitc(wb, prec, stream)
+            ms_b, _, e_b, st_b = time_steps(op_b, out, nst, 1, profile=name == "fp32")
+            res_b[name] = (ms_b, e_b[-1][0], st_b)
+            op_b.close()
+        ms_b, e_b, st_b = res_b["fp32"]
+        bitc = {"workload": wb.name, "value": wb.npairs / (ms_b / 1e3), "ms_per_step": ms_b, "energy_Ha": e_b,
+                "fp64_ms_per_step": res_b["fp64"][0], "fp64_energy_Ha": res_b["fp64"][1],
+                "energy_rel_err_fp32_vs_fp64": abs(e_b - res_b["fp64"][1]) / abs(res_b["fp64"][1]),
+                "kernels_ms_per_step": {k: v["ms"] / args.steps for k, v in st_b.items() if v["ms"] > 0}}
+        log(f"bitc fp32: {ms_b:.2f} ms/step, E = {e_b:.12f}; fp64 {res_b['fp64'][0]:.2f} ms/step")
+
     # dominant kernel and its roofline (algorithmic bytes / event-timed duration)
     dom = max(stats.items(), key=lambda kv: kv[1]["ms"])
     name, st = dom
@@ -251,6 +286,7 @@ def main():
         "fp32_splitbf16_gpu": dict(split, energy_rel_err_vs_fp64=(abs(split["energy_Ha"] - fp64["energy_Ha"])
                                                                   / abs(fp64["energy_Ha"])) if fp64 else None)
         if split else None,
+        "bitc_fp32_gpu": bitc,
         "stages_ms": dict(zip(tc.STAGES, stages)),
         "kernels_ms_per_step": per_kernel,
         "kernel_ms_per_step_total": total_kernel_ms,

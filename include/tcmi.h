@@ -9,7 +9,9 @@
  * (Sec. 2.5; Eqs. divcorr_2ax_scf, divcor_3a2_first/second in their
  * general-overlap form, 3b6_div_scf1-3).  It also returns the TC pseudo-energy
  * (Eq. EtotTC) and its gradient with respect to the orbital coefficients and
- * the Jastrow parameters A and C of Eq. Jastrow.
+ * the Jastrow parameters A and C of Eq. Jastrow.  With left orbitals loaded it
+ * works in the biorthogonal mode (BITC, Sec. 2.3, Eqs. BITCSCF and EtotBiTC):
+ * every bra, density and overlap takes conj(chi) in place of conj(phi).
  *
  * Conventions shared by every call
  *  - All calls return an int status: TC_OK (0) or a negative TC_ERR_* code;
@@ -76,7 +78,7 @@ enum {
 
 /* Energy breakdown written by tc_energy (hartree per cell, both spins). */
 enum {
-  TC_E_KINETIC = 0,   /* sum f <phi|-lap/2|phi> / N_k                                    */
+  TC_E_KINETIC = 0,   /* sum f <chi|-lap/2|phi> / N_k (chi = phi in TC mode)             */
   TC_E_TWO_BODY = 1,  /* (1/2) <h2>, h2 = 2ah+2bh1+2bh2+2ax+2bx1+2bx2 (+2ax correction)   */
   TC_E_THREE_BODY = 2,/* (1/3) <h3>, three-body terms with multiplicities (+ corrections)  */
   TC_E_CORR = 3,      /* part of the two entries above that comes from the corrections    */
@@ -123,14 +125,23 @@ int tc_set_jastrow(tc_ctx* ctx, const double A[2], const double C[2]);
 int tc_set_options(tc_ctx* ctx, int precision, double alpha, int div_correction, uint64_t term_mask);
 
 /* Copy the occupied orbitals of k-point ik to the device: `right` holds nband x
- * npw(ik) complex128 coefficients, `left` must be NULL (TC mode, chi = phi; the
- * biorthogonal mode is not built in this version: TC_ERR_UNSUPPORTED), `occ`
- * holds nband fillings per spin-orbital in [0, 1].  nband must be the same for
- * every k-point.  The coefficients are used as given (no re-orthonormalisation). */
+ * npw(ik) complex128 coefficients, `occ` nband fillings per spin-orbital in [0, 1].
+ * nband must be the same for every k-point.
+ * left == NULL: TC mode (chi = phi); the coefficients are used as given.
+ * left != NULL (same layout as right): biorthogonal mode for this k-point.  The
+ *   library makes the pair biorthonormal in FP64 on the device, as Sec. 2.3
+ *   requires (<chi_i|phi_j> = delta_ij, <phi_i|phi_i> = 1): each right orbital is
+ *   normalised, S_ij = <chi_i|phi_j> is formed and inverted (Gauss-Jordan with
+ *   partial pivoting) and the left set becomes conj(S^-1) chi.  TC_ERR_ARG if a
+ *   right orbital is zero or S is singular (a pivot not above 1e-13 max|S_ij|); the
+ *   k-point is then left unloaded.  Either every k-point or none must have left
+ *   orbitals when the operator is applied (else TC_ERR_STATE).  The energy
+ *   gradient (tc_energy_backward*) is built for TC mode only: TC_ERR_UNSUPPORTED in
+ *   the biorthogonal mode. */
 int tc_load_orbitals(tc_ctx* ctx, int ik, int nband, const double* right, const double* left,
                      const double* occ);
 
-/* Same, from a device buffer (complex128, [nband][npw(ik)]); occ stays on the host. */
+/* Same, TC mode, from a device buffer (complex128, [nband][npw(ik)]); occ stays on the host. */
 int tc_load_orbitals_dev(tc_ctx* ctx, int ik, int nband, const void* right_dev, const double* occ);
 
 /* Apply the selected two- and three-body terms (with corrections) to every
@@ -144,8 +155,9 @@ int tc_apply_all(tc_ctx* ctx, double* out);
  * the result then stays inside the context).  Asynchronous on the stream. */
 int tc_apply_all_dev(tc_ctx* ctx, void* out_dev);
 
-/* Pseudo-energy per cell (reading of Eq. EtotTC: (1/N_k) Re sum_{sigma,k,mu} f
- * <phi| T + h2/2 + h3/3 |phi>) of the last application (runs one if needed).
+/* Pseudo-energy per cell (reading of Eqs. EtotTC / EtotBiTC: (1/N_k) Re sum_{sigma,k,mu}
+ * f <chi| T + h2/2 + h3/3 |phi>, chi = phi in TC mode) of the last application (runs
+ * one if needed).
  * e_parts: NULL or TC_E_NPARTS doubles. */
 int tc_energy(tc_ctx* ctx, double* e_total, double* e_parts);
 
@@ -209,7 +221,8 @@ enum {
   TC_K_FUSED_Y = 15,    /* k_fused_Y: inverse xy + partner sums, 3b6 chain and pass B   */
   TC_K_OTHER = 16,      /* densities, Hartree-type fields, local terms, gathers          */
   TC_K_CORR = 17,       /* FP64 corrections, overlaps and kinetic energy                 */
-  TC_K_NKERNEL = 18
+  TC_K_FUSED_OB = 18,   /* k_fused_OB: occupied-occupied pass with left orbitals (BITC)  */
+  TC_K_NKERNEL = 19
 };
 
 /* Enable (1) or disable (0) per-kernel event timing for later applications. */

@@ -30,7 +30,8 @@ E_PARTS = ("kinetic", "two_body", "three_body", "corrections")
 KERNELS = ("k_scatter", "k_fft_xy<R,N,-1>", "k_fft_xy<R,N,1>", "k_fft_z<R,N,-1>", "k_fft_z<R,N,1>",
            "k_pair_xy<R,N,true>", "k_pair_xy<R,N,false>", "k_sum_parts<R,N>", "k_passB_xy<R,N>",
            "k_zconv<R,N,OP_O>", "k_zconv<R,N,OP_A1>", "k_zconv<R,N,OP_A2>", "k_zconv<R,N,OP_B>",
-           "k_fused_O<R,N>", "k_fused_A<R,N>", "k_fused_Y<R,N>", "other", "fp64_corrections")
+           "k_fused_O<R,N>", "k_fused_A<R,N>", "k_fused_Y<R,N>", "other", "fp64_corrections",
+           "k_fused_OB<R,N>")
 STAGES = ("g_to_r", "hartree", "occ_occ", "pass_a", "pass_b", "out_and_corrections")
 
 _lib = None
@@ -141,11 +142,19 @@ class TCOperator:
         self._check(self._L.tc_set_options(self._h, int(precision), float(alpha), int(bool(div_correction)),
                                            int(terms)), "tc_set_options")
 
-    def load_orbitals(self, ik, coeff, occ):
+    def load_orbitals(self, ik, coeff, occ, left=None):
+        """Right orbitals ``coeff`` (nband, npw) of k-point ik; ``left`` (same shape) switches that k-point to
+        the biorthogonal mode (the library normalises the right set and biorthogonalises the left one)."""
         c = np.ascontiguousarray(np.asarray(coeff, dtype=np.complex128))
         o = np.ascontiguousarray(np.asarray(occ, dtype=np.float64))
+        lp = None
+        if left is not None:
+            lc = np.ascontiguousarray(np.asarray(left, dtype=np.complex128))
+            if lc.shape != c.shape:
+                raise ValueError("left and right coefficient arrays differ in shape")
+            lp = _dp(lc.view(np.float64))
         self.nband = c.shape[0]
-        self._check(self._L.tc_load_orbitals(self._h, ik, c.shape[0], _dp(c.view(np.float64)), None, _dp(o)),
+        self._check(self._L.tc_load_orbitals(self._h, ik, c.shape[0], _dp(c.view(np.float64)), lp, _dp(o)),
                     "tc_load_orbitals")
 
     def load_orbitals_dev(self, ik, ptr: int, nband: int, occ):
@@ -221,8 +230,9 @@ class TCOperator:
 
 
 def from_workload(w, precision=TC_PREC_FP64, terms=TERM_ALL, div_correction=True, device=0, A=None, C=None,
-                  coeff=None, stream=None, batch=0) -> TCOperator:
-    """Build an operator from a ``tcinputs.Workload`` (TC mode)."""
+                  coeff=None, stream=None, batch=0, left=None) -> TCOperator:
+    """Build an operator from a ``tcinputs.Workload``: TC mode, or the biorthogonal mode when the workload
+    (or ``left``) holds left orbitals."""
     op = TCOperator(device, stream)
     if batch:
         op.set_batch(batch)
@@ -234,8 +244,9 @@ def from_workload(w, precision=TC_PREC_FP64, terms=TERM_ALL, div_correction=True
     op.set_jastrow(w.A if A is None else A, w.C if C is None else C)
     op.set_options(precision, w.alpha, div_correction, terms)
     cs = w.right if coeff is None else coeff
+    ls = w.left if left is None else left
     for ik in range(len(w.miller)):
-        op.load_orbitals(ik, cs[ik], w.occ[ik])
+        op.load_orbitals(ik, cs[ik], w.occ[ik], None if ls is None else ls[ik])
     return op
 
 

@@ -151,6 +151,8 @@ struct Problem {
   int nb = 0;
   std::vector<double> occ;                // [nk][nb]
   std::vector<char> loaded;               // per k
+  std::vector<char> left;                 // per k: loaded with left orbitals
+  bool bitc = false;                      // every k-point has left orbitals (set by prepare)
   double delta_gb = 0, sigma_aux = 0;
   int batch = 0;                          // targets per batch (0 = automatic)
 
@@ -225,6 +227,9 @@ struct DBuf {
 
 struct Shared {                       // precision-independent device data
   DBuf<double> coef;                  // [P][npw_max] complex128
+  DBuf<double> coefL;                 // [P][npw_max] complex128 left orbitals (biorthogonal mode)
+  DBuf<double> bo_l, bo_s, bo_inv, bo_aug;   // biorthogonalisation of one k-point (FP64)
+  DBuf<int> bo_flag;
   DBuf<int> boxidx;                   // [nk][npw_max]
   DBuf<int> npw;                      // [nk]
   DBuf<double> kg;                    // [nk][npw_max][3]
@@ -270,14 +275,17 @@ __global__ void k_overlap(const double* a, const double* b, const int* npw, int 
   }
 }
 
-__global__ void k_kinetic(const double* c, const double* kg, const int* npw, int nb, int npw_max, double* t) {
+// t[p] = Re <chi_p| -lap/2 |psi_p> from the coefficients (Sec. 2.6.2); cl = c in TC mode
+__global__ void k_kinetic(const double* cl, const double* c, const double* kg, const int* npw, int nb, int npw_max,
+                          double* t) {
   const int p = blockIdx.x, k = p / nb;
   double s = 0;
   for (int g = threadIdx.x; g < npw[k]; g += blockDim.x) {
     const double* q = kg + (long(k) * npw_max + g) * 3;
     const double e = 0.5 * (q[0] * q[0] + q[1] * q[1] + q[2] * q[2]);
-    const double* x = c + 2 * (long(p) * npw_max + g);
-    s += e * (x[0] * x[0] + x[1] * x[1]);
+    const double* x = cl + 2 * (long(p) * npw_max + g);
+    const double* y = c + 2 * (long(p) * npw_max + g);
+    s += e * (x[0] * y[0] + x[1] * y[1]);
   }
   __shared__ double red[256];
   red[threadIdx.x] = s;
@@ -308,11 +316,134 @@ __global__ void k_grad_finish(const double* c, const double* out, const double* 
   o[1] = f * (out[2 * id + 1] + e * c[2 * id + 1]);
 }
 
+// ------------------------------------------------------------------ biorthogonalisation (FP64)
+// Sec. 2.3 (BITC): the left and right determinants are built from orbitals with <chi_i|phi_j> = delta_ij
+// and <phi_i|phi_i> = 1.  Per k-point each right orbital is normalised, S_ij = <chi_i|phi_j> is formed and
+// the left set becomes conj(S^-1) chi, for which <chi'_i|phi_j> = sum_m (S^-1)_im S_mj = delta_ij.
+
+// c_b <- c_b / ||c_b|| for the bands at c (one block per band); bad = 1 for a zero orbital
+__global__ void __launch_bounds__(256) k_bo_normalize(double* c, int npw, int npw_max, int* bad) {
+  double* x = c + 2 * long(blockIdx.x) * npw_max;
+  double s = 0;
+  for (int g = threadIdx.x; g < npw; g += blockDim.x) s += x[2 * g] * x[2 * g] + x[2 * g + 1] * x[2 * g + 1];
+  __shared__ double red[256];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int h = blockDim.x / 2; h > 0; h >>= 1) {
+    if (int(threadIdx.x) < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  const double nrm = sqrt(red[0]);
+  if (!(nrm > 0.0)) {
+    if (threadIdx.x == 0) bad[0] = 1;
+    return;
+  }
+  for (int g = threadIdx.x; g < npw; g += blockDim.x) {
+    x[2 * g] /= nrm;
+    x[2 * g + 1] /= nrm;
+  }
+}
+
+// Sinv = S^-1 of one nb x nb complex matrix (row-major, interleaved) by Gauss-Jordan elimination with
+// partial pivoting, one work-group; a: scratch of nb x 2nb + nb complex.  bad = 2 when a pivot is not
+// above 1e-13 max|S_ij| (singular overlap); Sinv is then left unwritten.
+__global__ void __launch_bounds__(256) k_bo_invert(const double* S, int nb, double* a, double* Sinv, int* bad) {
+  const int tid = threadIdx.x, nt = blockDim.x, W = 2 * nb;
+  double* fac = a + 2L * nb * W;   // column of elimination factors
+  __shared__ double smax;
+  __shared__ int piv, fail;
+  for (long e = tid; e < long(nb) * W; e += nt) {
+    const int i = int(e / W), j = int(e % W);
+    a[2 * e] = j < nb ? S[2 * (long(i) * nb + j)] : (j - nb == i ? 1.0 : 0.0);
+    a[2 * e + 1] = j < nb ? S[2 * (long(i) * nb + j) + 1] : 0.0;
+  }
+  if (tid == 0) {
+    double m = 0;
+    for (long e = 0; e < long(nb) * nb; ++e) m = fmax(m, hypot(S[2 * e], S[2 * e + 1]));
+    smax = m;
+    fail = !(m > 0.0);
+  }
+  __syncthreads();
+  for (int k = 0; k < nb && !fail; ++k) {
+    if (tid == 0) {
+      int p = k;
+      double best = -1.0;
+      for (int i = k; i < nb; ++i) {
+        const double v = hypot(a[2 * (long(i) * W + k)], a[2 * (long(i) * W + k) + 1]);
+        if (v > best) {
+          best = v;
+          p = i;
+        }
+      }
+      piv = p;
+      if (!(best > 1e-13 * smax)) fail = 1;
+    }
+    __syncthreads();
+    if (fail) break;
+    if (piv != k)
+      for (int j = tid; j < W; j += nt)
+        for (int c = 0; c < 2; ++c) {
+          const double t = a[2 * (long(k) * W + j) + c];
+          a[2 * (long(k) * W + j) + c] = a[2 * (long(piv) * W + j) + c];
+          a[2 * (long(piv) * W + j) + c] = t;
+        }
+    __syncthreads();
+    const double pr = a[2 * (long(k) * W + k)], pi = a[2 * (long(k) * W + k) + 1];
+    const double d = pr * pr + pi * pi, ir = pr / d, ii = -pi / d;
+    __syncthreads();
+    for (int j = tid; j < W; j += nt) {
+      const double xr = a[2 * (long(k) * W + j)], xi = a[2 * (long(k) * W + j) + 1];
+      a[2 * (long(k) * W + j)] = xr * ir - xi * ii;
+      a[2 * (long(k) * W + j) + 1] = xr * ii + xi * ir;
+    }
+    for (int i = tid; i < nb; i += nt) {
+      fac[2 * i] = a[2 * (long(i) * W + k)];
+      fac[2 * i + 1] = a[2 * (long(i) * W + k) + 1];
+    }
+    __syncthreads();
+    for (long e = tid; e < long(nb) * W; e += nt) {
+      const int i = int(e / W), j = int(e % W);
+      if (i == k) continue;
+      const double fr = fac[2 * i], fi = fac[2 * i + 1];
+      const double yr = a[2 * (long(k) * W + j)], yi = a[2 * (long(k) * W + j) + 1];
+      a[2 * e] -= fr * yr - fi * yi;
+      a[2 * e + 1] -= fr * yi + fi * yr;
+    }
+    __syncthreads();
+  }
+  if (fail) {
+    if (tid == 0 && bad[0] == 0) bad[0] = 2;   // a zero right orbital (1) is the more specific report
+    return;
+  }
+  for (long e = tid; e < long(nb) * nb; e += nt) {
+    const int i = int(e / nb), j = int(e % nb);
+    Sinv[2 * e] = a[2 * (long(i) * W + nb + j)];
+    Sinv[2 * e + 1] = a[2 * (long(i) * W + nb + j) + 1];
+  }
+}
+
+// out_i = sum_m conj(Sinv_im) l_m for the nb bands of one k-point ([nb][npw_max], zero beyond npw)
+__global__ void k_bo_left(const double* Sinv, const double* l, int nb, int npw, int npw_max, double* out) {
+  const long id = long(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (id >= long(nb) * npw_max) return;
+  const int i = int(id / npw_max), g = int(id - long(i) * npw_max);
+  double re = 0, im = 0;
+  if (g < npw)
+    for (int m = 0; m < nb; ++m) {
+      const double sr = Sinv[2 * (long(i) * nb + m)], si = Sinv[2 * (long(i) * nb + m) + 1];
+      const double xr = l[2 * (long(m) * npw_max + g)], xi = l[2 * (long(m) * npw_max + g) + 1];
+      re += sr * xr + si * xi;
+      im += sr * xi - si * xr;
+    }
+  out[2 * id] = re;
+  out[2 * id + 1] = im;
+}
+
 // Source of the G != 0 correction of 3a2 (Eq. divcor_3a2_second, general-overlap form):
-// Y = 2 sum_k sum_{m1,m2} (f_m1 f_m2 / N_k) (S(m1,m2)/Omega) conj(psi_m2) psi_m1   (TC mode)
+// Y = 2 sum_k sum_{m1,m2} (f_m1 f_m2 / N_k) (S(m1,m2)/Omega) conj(chi_m2) psi_m1, S(a,b) = <chi_a|psi_b>
 template <int N>
-__global__ void k_corr_Ysrc(const cx<double>* psi, const double* S, const double* f, int nk, int nb, double inv_nk_omega,
-                            cx<double>* Y) {
+__global__ void k_corr_Ysrc(const cx<double>* chi, const cx<double>* psi, const double* S, const double* f, int nk,
+                            int nb, double inv_nk_omega, cx<double>* Y) {
   constexpr long NR = long(N) * N * N;
   const long r = long(blockIdx.x) * blockDim.x + threadIdx.x;
   if (r >= NR) return;
@@ -322,7 +453,7 @@ __global__ void k_corr_Ysrc(const cx<double>* psi, const double* S, const double
       for (int m2 = 0; m2 < nb; ++m2) {
         const int i1 = k * nb + m1, i2 = k * nb + m2;
         const double sr = S[2 * ((k * nb + m1) * nb + m2)], si = S[2 * ((k * nb + m1) * nb + m2) + 1];
-        const cx<double> v = cmulc(psi[i2 * NR + r], psi[i1 * NR + r]);
+        const cx<double> v = cmulc(chi[i2 * NR + r], psi[i1 * NR + r]);
         const double c = 2.0 * f[i1] * f[i2] * inv_nk_omega;
         yr += c * (sr * v.x - si * v.y);
         yi += c * (sr * v.y + si * v.x);
@@ -352,14 +483,15 @@ __global__ void k_corr_products(const cx<double>* F, const cx<double>* psi, int 
   out[id] = F[fi * NR + r] * psi[p * NR + r];
 }
 
-// corrections in coefficient space (FP64):
+// corrections in coefficient space (FP64), S(a,b) = <chi_a|psi_b>, O(a,b) = <chi_a|F psi_b>:
 //  dhc2_j = -4 pi dGB sum_mu f_mu (S(mu,j)/Omega) c_mu                        (Eq. divcorr_2ax_scf)
 //  dhc3_j = 1/2 const1 c_j + 1/2 W_j                                          (3a2, Eqs. divcor_3a2_*)
 //         + 2 sum_mu f_mu { [c1s n0 S(mu,j)/Omega + O(mu,j)/Omega] c_mu + (S(mu,j)/Omega) Z_mu }  (3b6 x 2)
+// const1 and c1s n0 are complex (imaginary parts zero in TC mode).
 __global__ void k_corr_apply(const double* c, const double* S, const double* O, const double* Z, const double* W,
                              const double* f, const int* npw, int nb, int npw_max, int P, double omega, double m2ax,
-                             double dgb, double m3a2, double const1, double m3b6, double c1s_n0, double* dhc2,
-                             double* dhc3) {
+                             double dgb, double m3a2, double const1, double const1i, double m3b6, double c1s_n0,
+                             double c1s_n0i, double* dhc2, double* dhc3) {
   const long id = long(blockIdx.x) * blockDim.x + threadIdx.x;
   if (id >= long(P) * npw_max) return;
   const int j = int(id / npw_max), g = int(id - long(j) * npw_max);
@@ -378,13 +510,13 @@ __global__ void k_corr_apply(const double* c, const double* S, const double* O, 
       a2r += -kFourPi * dgb * f[q] * (sr * cq[0] - sim * cq[1]);
       a2i += -kFourPi * dgb * f[q] * (sr * cq[1] + sim * cq[0]);
       // 3b6 (x 2)
-      const double br = c1s_n0 * sr + orr, bi = c1s_n0 * sim + oi;
+      const double br = c1s_n0 * sr - c1s_n0i * sim + orr, bi = c1s_n0 * sim + c1s_n0i * sr + oi;
       a3r += 2.0 * m3b6 * f[q] * (br * cq[0] - bi * cq[1] + sr * zq[0] - sim * zq[1]);
       a3i += 2.0 * m3b6 * f[q] * (br * cq[1] + bi * cq[0] + sr * zq[1] + sim * zq[0]);
     }
     const double* wj = W + 2 * (long(j) * npw_max + g);
-    a3r += m3a2 * 0.5 * (const1 * cj[0] + wj[0]);
-    a3i += m3a2 * 0.5 * (const1 * cj[1] + wj[1]);
+    a3r += m3a2 * 0.5 * (const1 * cj[0] - const1i * cj[1] + wj[0]);
+    a3i += m3a2 * 0.5 * (const1 * cj[1] + const1i * cj[0] + wj[1]);
   }
   dhc2[2 * id] = m2ax * a2r;
   dhc2[2 * id + 1] = m2ax * a2i;
@@ -392,7 +524,7 @@ __global__ void k_corr_apply(const double* c, const double* S, const double* O, 
   dhc3[2 * id + 1] = a3i;
 }
 
-// out += dhc2 + dhc3;  ecorr[j] = (<c_j|dhc2_j>, <c_j|dhc3_j>) real parts
+// out += dhc2 + dhc3;  ecorr[j] = (<cl_j|dhc2_j>, <cl_j|dhc3_j>) real parts (cl: left coefficients, c in TC mode)
 __global__ void k_corr_add(const double* c, const double* dhc2, const double* dhc3, const int* npw, int nb,
                            int npw_max, double* out, double* ecorr) {
   const int j = blockIdx.x, k = j / nb;
@@ -424,18 +556,26 @@ __global__ void k_corr_add(const double* c, const double* dhc2, const double* dh
 }
 
 
-// density only (FP64 corrections): n = sum_q w_q |psi_q|^2
+// density only (FP64 corrections): n = sum_q w_q conj(chi_q) psi_q (chi = psi in TC mode)
 template <int N>
-__global__ void k_density64(const cx<double>* psi, const double* w, int P, cx<double>* n) {
+__global__ void k_density64(const cx<double>* chi, const cx<double>* psi, const double* w, int P, cx<double>* n) {
   constexpr long NR = long(N) * N * N;
   const long r = long(blockIdx.x) * blockDim.x + threadIdx.x;
   if (r >= NR) return;
-  double s = 0;
-  for (int q = 0; q < P; ++q) {
-    const cx<double> a = psi[q * NR + r];
-    s += w[q] * (a.x * a.x + a.y * a.y);
+  double s = 0, si = 0;
+  if (chi == psi) {
+    for (int q = 0; q < P; ++q) {
+      const cx<double> a = psi[q * NR + r];
+      s += w[q] * (a.x * a.x + a.y * a.y);
+    }
+  } else {
+    for (int q = 0; q < P; ++q) {
+      const cx<double> v = cmulc(chi[q * NR + r], psi[q * NR + r]);
+      s += w[q] * v.x;
+      si += w[q] * v.y;
+    }
   }
-  n[r] = {s, 0.0};
+  n[r] = {s, si};
 }
 
 inline unsigned nblk(long n, int b = 256) { return unsigned((n + b - 1) / b); }
@@ -585,6 +725,14 @@ struct EngineT : Engine {
   DBuf<cx<R>> h4part;       // [S][T][3][NR]
   DBuf<R> h5part;           // [S][T][NR]
   DBuf<cx<R>> H3part;       // [S][T][3][NR]
+  // biorthogonal mode (left orbitals chi != psi)
+  DBuf<cx<R>> chi;          // [P][NR]
+  DBuf<cx<R>> H3bc;         // [P][3][NR]  conj(H3b) (Cartesian), then its lattice components B conj(H3b)
+  DBuf<cx<R>> h5c;          // [P][NR]  complex h5
+  DBuf<cx<R>> h5cpart;      // [S][T][NR]
+  DBuf<cx<R>> Hbpart;       // [S][T][3][NR]
+  DBuf<cx<double>> chi64;   // [P][NR]  FP64 left orbitals for the corrections
+  bool bitc_alloc = false;
   int S = 1;
   // kernel tables (scaled by 1/(Omega N^3))
   DBuf<R> tV, tU1, tU2, tHV, tHU;
@@ -751,23 +899,28 @@ struct EngineT : Engine {
   }
 
   template <int OP>
-  void zconv(hipStream_t s, long npair, int t0, const MeshInfo& mi, const Tables& tb, int sign) {
+  void zconv(hipStream_t s, const cx<R>* in, cx<R>* out, long npair, int t0, const MeshInfo& mi, const Tables& tb,
+             int sign) {
     if constexpr (std::is_same<R, float>::value && N % 8 == 0) {
       if (zmfma) {
         const long groups = npair * (long(N) * N / 16);
         const unsigned nb = unsigned(std::min<long>((groups + 3) / 4, 8192));
-        hipLaunchKernelGGL((k_zconv_mfma<N, OP>), dim3(nb), dim3(256), 0, s, bufA.p, bufB.p, npair, t0, mi, tb, sign,
+        hipLaunchKernelGGL((k_zconv_mfma<N, OP>), dim3(nb), dim3(256), 0, s, in, out, npair, t0, mi, tb, sign,
                            reinterpret_cast<const bf16x4*>(zfrag.p));
         return;
       }
     }
-    hipLaunchKernelGGL((k_zconv<R, N, OP>), dim3(nblk(npair * N * N)), dim3(256), 0, s, bufA.p, bufB.p, npair, t0, mi,
-                       tb, sign);
+    hipLaunchKernelGGL((k_zconv<R, N, OP>), dim3(nblk(npair * N * N)), dim3(256), 0, s, in, out, npair, t0, mi, tb,
+                       sign);
+  }
+  template <int OP>
+  void zconv(hipStream_t s, long npair, int t0, const MeshInfo& mi, const Tables& tb, int sign) {
+    zconv<OP>(s, bufA.p, bufB.p, npair, t0, mi, tb, sign);
   }
 
   void ensure(const Problem& pb, size_t budget_bytes) {
     const int P = pb.P();
-    if (P == P_alloc && pb.batch == batch_alloc) return;
+    if (P == P_alloc && pb.batch == batch_alloc && pb.bitc == bitc_alloc) return;
     psi.alloc(size_t(P) * NR);
     D.alloc(size_t(3) * P * NR);
     Dl.alloc(size_t(3) * P * NR);
@@ -777,11 +930,14 @@ struct EngineT : Engine {
     wk.alloc(9 * NR);
     H3a4.alloc(size_t(3) * P * NR);
     h5.alloc(size_t(P) * NR);
-    const size_t per_t = size_t(P) * 9 * NR * sizeof(cx<R>);
+    // per target: 4 pair fields in bufA and 5 in bufB (8 in biorthogonal mode: V21 and V12 of the
+    // occupied-occupied pass)
+    const int nB = pb.bitc ? 8 : 5;
+    const size_t per_t = size_t(P) * (4 + nB) * NR * sizeof(cx<R>);
     T = int(std::max<size_t>(1, std::min<size_t>(size_t(P), budget_bytes / per_t)));
     if (pb.batch > 0) T = std::min(pb.batch, P);
     bufA.alloc(size_t(T) * P * 4 * NR);
-    bufB.alloc(size_t(T) * P * 5 * NR);
+    bufB.alloc(size_t(T) * P * nB * NR);
     h4.alloc(size_t(3) * T * NR);
     Z.alloc(size_t(3) * T * NR);
     g.alloc(size_t(T) * NR);
@@ -797,8 +953,17 @@ struct EngineT : Engine {
     v64.alloc(4 * NR);
     prod64.alloc(size_t(2) * P * NR);
     focc.alloc(P);
+    if (pb.bitc) {
+      chi.alloc(size_t(P) * NR);
+      H3bc.alloc(size_t(3) * P * NR);
+      h5c.alloc(size_t(P) * NR);
+      h5cpart.alloc(size_t(S) * T * NR);
+      Hbpart.alloc(size_t(S) * 3 * T * NR);
+      chi64.alloc(size_t(P) * NR);
+    }
     P_alloc = P;
     batch_alloc = pb.batch;
+    bitc_alloc = pb.bitc;
   }
 
   void apply(hipStream_t s, Shared& sh, const Problem& pb, double* stage_ms) override {
@@ -815,6 +980,9 @@ struct EngineT : Engine {
       for (int e = 0; e < 3; ++e)
         mm.b[3 * d + e] = R(pb.B[3 * d] * pb.B[3 * e] + pb.B[3 * d + 1] * pb.B[3 * e + 1] + pb.B[3 * d + 2] * pb.B[3 * e + 2]);
     const Tables tb{tV.p, tU1.p, tU2.p, dfr.p};
+    // biorthogonal mode: bras use the left orbitals chi; TC mode: chi = psi (same array)
+    const bool bitc = pb.bitc;
+    const cx<R>* X = bitc ? chi.p : psi.p;
     // algorithmic bytes: fields each launch must read or write once (working precision)
     const double fb = double(sizeof(cx<R>)) * NR;
     const double fd = double(sizeof(cx<double>)) * NR;
@@ -831,6 +999,7 @@ struct EngineT : Engine {
     // ---- 0: G -> r (psi and the three components of D)
     TC_HIP(hipMemsetAsync(psi.p, 0, size_t(P) * NR * sizeof(cx<R>), s));
     TC_HIP(hipMemsetAsync(D.p, 0, size_t(3) * P * NR * sizeof(cx<R>), s));
+    if (bitc) TC_HIP(hipMemsetAsync(chi.p, 0, size_t(P) * NR * sizeof(cx<R>), s));
     const unsigned gsc = nblk(long(P) * pb.npw_max);
     K(TC_K_SCATTER, 0.0, [&] {
       hipLaunchKernelGGL((k_scatter<R>), dim3(gsc), dim3(256), 0, s, sh.coef.p, sh.boxidx.p, sh.npw.p, sh.kg.p, nb,
@@ -838,8 +1007,12 @@ struct EngineT : Engine {
       for (int c = 0; c < 3; ++c)
         hipLaunchKernelGGL((k_scatter<R>), dim3(gsc), dim3(256), 0, s, sh.coef.p, sh.boxidx.p, sh.npw.p, sh.kg.p, nb,
                            pb.npw_max, P, c, D.p + size_t(c) * P * NR, NR);
+      if (bitc)
+        hipLaunchKernelGGL((k_scatter<R>), dim3(gsc), dim3(256), 0, s, sh.coefL.p, sh.boxidx.p, sh.npw.p, sh.kg.p, nb,
+                           pb.npw_max, P, -1, chi.p, NR);
     });
     fft3d_t<R, N>(psi.p, P, +1, s, pf);
+    if (bitc) fft3d_t<R, N>(chi.p, P, +1, s, pf);
     fft3d_t<R, N>(D.p, 3L * P, +1, s, pf);
     K(TC_K_OTHER, 6.0 * fb * P, [&] {
       hipLaunchKernelGGL((k_lattice3<R, N>), dim3(nblk(long(P) * NR)), dim3(256), 0, s, D.p, Dl.p, bm, long(P), NR,
@@ -850,7 +1023,8 @@ struct EngineT : Engine {
     // ---- 1: densities and Hartree-type fields (Algs. 2ah, 3a1, 3b1; 2bh1, 2bh2)
     TC_HIP(hipMemsetAsync(loc.p, 0, 8 * NR * sizeof(cx<R>), s));
     K(TC_K_OTHER, fb * (4.0 * P + 4.0), [&] {
-      hipLaunchKernelGGL((k_density<R, N>), dim3(nblk(NR)), dim3(256), 0, s, psi.p, D.p, sh.w.p, P, nJ.p, nJ.p + NR);
+      hipLaunchKernelGGL((k_density<R, N>), dim3(nblk(NR)), dim3(256), 0, s, X, psi.p, D.p, sh.w.p, P, nJ.p,
+                         nJ.p + NR);
     });
     TC_HIP(hipMemcpyAsync(wk.p, nJ.p, 4 * NR * sizeof(cx<R>), hipMemcpyDeviceToDevice, s));
     fft3d_t<R, N>(wk.p, 4, -1, s, pf);
@@ -875,30 +1049,60 @@ struct EngineT : Engine {
     const bool need_occ = m.m3a2 || m.m3a4 || m.m3b2 || m.m3b5;
     const int chunk = (P + S - 1) / S;
     TC_HIP(hipMemsetAsync(H3a4.p, 0, size_t(3) * P * NR * sizeof(cx<R>), s));
+    if (bitc) TC_HIP(hipMemsetAsync(H3bc.p, 0, size_t(3) * P * NR * sizeof(cx<R>), s));
     if (need_occ) {
       for (int a0 = 0; a0 < P; a0 += T) {
         const int nt = std::min(T, P - a0);
         const long npair = long(nt) * P;
         const FusedArgs fa{P, nt, a0, S, chunk};
-        K(TC_K_XY_PAIR_OCC, fb * (npair + nt + P), [&] {
-          hipLaunchKernelGGL((k_pair_xy<R, N, true>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, psi.p, fa,
-                             bufA.p);
-        });
-        K(TC_K_ZCONV_OCC, fb * 5.0 * npair + tabB, [&] {
-          zconv<OP_O>(s, npair, a0, mi, tb, 0);
-        });
-        K(TC_K_FUSED_O, fb * (4.0 * npair + P) + 3.5 * fb * nt * S, [&] {
-          hipLaunchKernelGGL((k_fused_O<R, N>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, bufB.p, psi.p, sh.w.p,
-                             fa, mi, rc, dfr.p, h5part.p, H3part.p);
-        });
-        K(TC_K_SUM_PARTS, 4.0 * fb * nt * (S + 1), [&] {
-          hipLaunchKernelGGL((k_sum_parts<R, N>), dim3(nblk(long(nt) * NR)), dim3(256), 0, s, 0, S, nt, a0, 0,
-                             h5part.p, H3part.p, nullptr, nullptr, h5.p, H3a4.p, nullptr, nullptr);
-        });
+        if (!bitc) {
+          K(TC_K_XY_PAIR_OCC, fb * (npair + nt + P), [&] {
+            hipLaunchKernelGGL((k_pair_xy<R, N, true>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, psi.p, psi.p,
+                               fa, bufA.p);
+          });
+          K(TC_K_ZCONV_OCC, fb * 5.0 * npair + tabB, [&] {
+            zconv<OP_O>(s, npair, a0, mi, tb, 0);
+          });
+          K(TC_K_FUSED_O, fb * (4.0 * npair + P) + 3.5 * fb * nt * S, [&] {
+            hipLaunchKernelGGL((k_fused_O<R, N>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, bufB.p, psi.p, sh.w.p,
+                               fa, mi, rc, dfr.p, h5part.p, H3part.p);
+          });
+          K(TC_K_SUM_PARTS, 4.0 * fb * nt * (S + 1), [&] {
+            hipLaunchKernelGGL((k_sum_parts<R, N>), dim3(nblk(long(nt) * NR)), dim3(256), 0, s, 0, S, nt, a0, 0,
+                               h5part.p, H3part.p, nullptr, nullptr, h5.p, H3a4.p, nullptr, nullptr);
+          });
+        } else {
+          // rho21 = conj(chi_a) psi_b and rho12 = conj(chi_b) psi_a, a = a0 + t, b = q; V21 at Delta = k_b - k_a,
+          // V12 at Delta = k_a - k_b (no conjugate symmetry between them)
+          cx<R>* in12 = bufA.p + npair * NR;
+          cx<R>* out12 = bufB.p + 4 * npair * NR;
+          K(TC_K_XY_PAIR_OCC, fb * 2.0 * (npair + nt + P), [&] {
+            hipLaunchKernelGGL((k_pair_xy<R, N, true>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, X, psi.p, fa,
+                               bufA.p);
+            hipLaunchKernelGGL((k_pair_xy<R, N, false>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, X, psi.p, fa,
+                               in12);
+          });
+          K(TC_K_ZCONV_OCC, 2.0 * (fb * 5.0 * npair + tabB), [&] {
+            zconv<OP_O>(s, bufA.p, bufB.p, npair, a0, mi, tb, 0);
+            zconv<OP_O>(s, in12, out12, npair, a0, mi, tb, 1);
+          });
+          K(TC_K_FUSED_OB, fb * (8.0 * npair + 2.0 * P) + 7.0 * fb * nt * S, [&] {
+            hipLaunchKernelGGL((k_fused_OB<R, N>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, bufB.p, out12, psi.p,
+                               X, sh.w.p, fa, mi, rc, dfr.p, h5cpart.p, H3part.p, Hbpart.p);
+          });
+          K(TC_K_SUM_PARTS, 7.0 * fb * nt * (S + 1), [&] {
+            hipLaunchKernelGGL((k_sum_parts_ob<R, N>), dim3(nblk(long(nt) * NR)), dim3(256), 0, s, S, nt, a0,
+                               h5cpart.p, H3part.p, Hbpart.p, h5c.p, H3a4.p, H3bc.p);
+          });
+        }
       }
       K(TC_K_OTHER, fb * (5.0 * P + 4.0), [&] {
-        hipLaunchKernelGGL((k_reduce_occ<R, N>), dim3(nblk(NR)), dim3(256), 0, s, h5.p, H3a4.p, psi.p, sh.w.p, P,
-                           loc.p + 6 * NR, wk.p);
+        if (bitc)
+          hipLaunchKernelGGL((k_reduce_occ<R, N, cx<R>>), dim3(nblk(NR)), dim3(256), 0, s, h5c.p, H3bc.p, psi.p,
+                             sh.w.p, P, loc.p + 6 * NR, wk.p);
+        else
+          hipLaunchKernelGGL((k_reduce_occ<R, N, R>), dim3(nblk(NR)), dim3(256), 0, s, h5.p, H3a4.p, psi.p, sh.w.p,
+                             P, loc.p + 6 * NR, wk.p);
       });
       fft3d_t<R, N>(wk.p, 3, -1, s, pf);
       K(TC_K_OTHER, fb * 4.0, [&] {
@@ -910,6 +1114,9 @@ struct EngineT : Engine {
     K(TC_K_OTHER, 6.0 * fb * P, [&] {
       hipLaunchKernelGGL((k_lattice3<R, N>), dim3(nblk(long(P) * NR)), dim3(256), 0, s, H3a4.p, Hl.p, bm, long(P),
                          3 * NR, NR);
+      if (bitc)   // in place: B conj(H3b), the pass-B partner field
+        hipLaunchKernelGGL((k_lattice3<R, N>), dim3(nblk(long(P) * NR)), dim3(256), 0, s, H3bc.p, H3bc.p, bm,
+                           long(P), 3 * NR, NR);
     });
     TC_HIP(hipEventRecord(ev.e[3], s));
 
@@ -932,7 +1139,7 @@ struct EngineT : Engine {
       if (need_A) {
         const FusedArgs fa{P, nt, t0, S, chunk};
         K(TC_K_XY_PAIR_TGT, fb * (npair + nt + P), [&] {
-          hipLaunchKernelGGL((k_pair_xy<R, N, false>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, psi.p, fa,
+          hipLaunchKernelGGL((k_pair_xy<R, N, false>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, X, psi.p, fa,
                              bufA.p);
         });
         K(TC_K_ZCONV_A1, fb * 6.0 * npair + tabB, [&] {
@@ -969,8 +1176,8 @@ struct EngineT : Engine {
                              h4.p, t0, nt, P, m, bm, Z.p);
         });
         K(TC_K_XY_PASSB, fb * (2.0 * npair + 4.0 * P + 4.0 * nt), [&] {
-          hipLaunchKernelGGL((k_passB_xy<R, N>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, psi.p, Z.p, Hl.p, fy,
-                             mi, dfr.p, R(m.m3b5), bufA.p);
+          hipLaunchKernelGGL((k_passB_xy<R, N>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, psi.p, X, Z.p,
+                             bitc ? H3bc.p : Hl.p, fy, mi, dfr.p, R(m.m3b5), bufA.p);
         });
         K(TC_K_ZCONV_B, fb * 3.0 * npair + tabB, [&] {
           zconv<OP_B>(s, npair, t0, mi, tb, 1);
@@ -988,7 +1195,7 @@ struct EngineT : Engine {
       K(TC_K_OTHER, fb * 16.0 * nt + 8.0 * fd * nt, [&] {
         hipLaunchKernelGGL((k_local<R, N>), dim3(nblk(long(nt) * NR)), dim3(256), 0, s, psi.p, D.p, loc.p, h4.p, t0,
                            nt, P, m, acc.p, g.p);
-        hipLaunchKernelGGL((k_epart<R, N>), dim3(4 * nt), dim3(256), 0, s, psi.p, acc.p, t0, nt, sh.epart.p);
+        hipLaunchKernelGGL((k_epart<R, N>), dim3(4 * nt), dim3(256), 0, s, X, acc.p, t0, nt, sh.epart.p);
       });
       fft3d_t<R, N>(g.p, nt, -1, s, pf);
       K(TC_K_OTHER, 0.0, [&] {
@@ -1000,8 +1207,8 @@ struct EngineT : Engine {
 
     // ---- 5: kinetic energy and FP64 corrections
     K(TC_K_CORR, 0.0, [&] {
-      hipLaunchKernelGGL(k_kinetic, dim3(P), dim3(256), 0, s, sh.coef.p, sh.kg.p, sh.npw.p, nb, pb.npw_max,
-                         sh.tkin.p);
+      hipLaunchKernelGGL(k_kinetic, dim3(P), dim3(256), 0, s, bitc ? sh.coefL.p : sh.coef.p, sh.coef.p, sh.kg.p,
+                         sh.npw.p, nb, pb.npw_max, sh.tkin.p);
       TC_HIP(hipMemsetAsync(sh.ecorr.p, 0, size_t(2) * P * sizeof(double), s));
       if (pb.div && (pb.mask & TC_T_CORR) && (m.m2ax || m.m3a2 || m.m3b6)) corrections(s, sh, pb, m);
     });
@@ -1026,10 +1233,14 @@ struct EngineT : Engine {
   }
 
   // SCF-mesh divergence corrections in FP64 (2ax, 3a2, 3b6); see k_corr_apply.
+  // Biorthogonal mode: overlaps S(a,b) = <chi_a|psi_b>, densities and 3a2 sources with conj(chi),
+  // energies with <chi|.
   void corrections(hipStream_t s, Shared& sh, const Problem& pb, const Masks& m) {
     const int P = pb.P(), nb = pb.nb, nk = pb.nk;
-    hipLaunchKernelGGL(k_overlap, dim3(nk * nb * nb), dim3(256), 0, s, sh.coef.p, sh.coef.p, sh.npw.p, nb,
-                       pb.npw_max, nk, sh.S.p);
+    const bool bitc = pb.bitc;
+    const double* cl = bitc ? sh.coefL.p : sh.coef.p;
+    hipLaunchKernelGGL(k_overlap, dim3(nk * nb * nb), dim3(256), 0, s, cl, sh.coef.p, sh.npw.p, nb, pb.npw_max, nk,
+                       sh.S.p);
     std::vector<double> S(size_t(2) * nk * nb * nb);
     TC_HIP(hipMemcpyAsync(S.data(), sh.S.p, S.size() * sizeof(double), hipMemcpyDeviceToHost, s));
     TC_HIP(hipMemcpyAsync(focc.p, pb.occ.data(), P * sizeof(double), hipMemcpyHostToDevice, s));
@@ -1038,12 +1249,19 @@ struct EngineT : Engine {
     hipLaunchKernelGGL((k_scatter<double>), dim3(nblk(long(P) * pb.npw_max)), dim3(256), 0, s, sh.coef.p, sh.boxidx.p,
                        sh.npw.p, sh.kg.p, nb, pb.npw_max, P, -1, psi64.p, NR);
     fft3d_t<double, N>(psi64.p, P, +1, s);
+    if (bitc) {
+      TC_HIP(hipMemsetAsync(chi64.p, 0, size_t(P) * NR * sizeof(cx<double>), s));
+      hipLaunchKernelGGL((k_scatter<double>), dim3(nblk(long(P) * pb.npw_max)), dim3(256), 0, s, sh.coefL.p,
+                         sh.boxidx.p, sh.npw.p, sh.kg.p, nb, pb.npw_max, P, -1, chi64.p, NR);
+      fft3d_t<double, N>(chi64.p, P, +1, s);
+    }
+    const cx<double>* X64 = bitc ? chi64.p : psi64.p;
     cx<double>* nG = v64.p;
     cx<double>* YG = v64.p + NR;
     cx<double>* F1 = v64.p + 2 * NR;
     cx<double>* F2 = v64.p + 3 * NR;
-    hipLaunchKernelGGL((k_density64<N>), dim3(nblk(NR)), dim3(256), 0, s, psi64.p, sh.w.p, P, nG);
-    hipLaunchKernelGGL((k_corr_Ysrc<N>), dim3(nblk(NR)), dim3(256), 0, s, psi64.p, sh.S.p, focc.p, nk, nb,
+    hipLaunchKernelGGL((k_density64<N>), dim3(nblk(NR)), dim3(256), 0, s, X64, psi64.p, sh.w.p, P, nG);
+    hipLaunchKernelGGL((k_corr_Ysrc<N>), dim3(nblk(NR)), dim3(256), 0, s, X64, psi64.p, sh.S.p, focc.p, nk, nb,
                        1.0 / (nk * pb.omega), YG);
     fft3d_t<double, N>(nG, 2, -1, s);
     const double a0 = 2 * kPi * corrA[0] / nk, a1 = 2 * kPi * corrA[1] / nk;
@@ -1057,32 +1275,37 @@ struct EngineT : Engine {
     hipLaunchKernelGGL((k_gather<double>), dim3(nblk(long(P) * pb.npw_max)), dim3(256), 0, s,
                        prod64.p + size_t(P) * NR, sh.boxidx.p, sh.npw.p, nb, pb.npw_max, 0, P, 1.0 / double(NR),
                        sh.Wg.p, NR);
-    hipLaunchKernelGGL(k_overlap, dim3(nk * nb * nb), dim3(256), 0, s, sh.coef.p, sh.Zg.p, sh.npw.p, nb, pb.npw_max,
-                       nk, sh.O.p);
+    hipLaunchKernelGGL(k_overlap, dim3(nk * nb * nb), dim3(256), 0, s, cl, sh.Zg.p, sh.npw.p, nb, pb.npw_max, nk,
+                       sh.O.p);
     TC_HIP(hipStreamSynchronize(s));
     // scalars: n~(0) per spin and const1 of the G = G' = 0 correction of 3a2
-    double n0 = 0;
+    double n0 = 0, n0i = 0;   // n~(0) = sum_a w_a S(a,a) / Omega (real in TC mode)
     for (int k = 0; k < nk; ++k)
-      for (int a = 0; a < nb; ++a) n0 += pb.occ[k * nb + a] / nk * S[2 * ((k * nb + a) * nb + a)] / pb.omega;
+      for (int a = 0; a < nb; ++a) {
+        n0 += pb.occ[k * nb + a] / nk * S[2 * ((k * nb + a) * nb + a)] / pb.omega;
+        if (bitc) n0i += pb.occ[k * nb + a] / nk * S[2 * ((k * nb + a) * nb + a) + 1] / pb.omega;
+      }
     double c1s = 0, c1a = 0;
     for (int ch = 0; ch < 2; ++ch) {
       c1s += 2 * kPi * corrB[ch];   // Eq. 3b6_div_scf1 (summed over the density's spin)
       c1a += kFourPi * corrB[ch];   // Eq. divcor_3a2_first (summed over the partners' spin)
     }
-    double const1 = 0;
+    double const1 = 0, const1i = 0;   // sum f_a f_b S(a,b) S(b,a) (real in TC mode)
     for (int k = 0; k < nk; ++k)
       for (int a = 0; a < nb; ++a)
         for (int b = 0; b < nb; ++b) {
           const double* sab = &S[2 * ((k * nb + a) * nb + b)];
           const double* sba = &S[2 * ((k * nb + b) * nb + a)];
           const double re = sab[0] * sba[0] - sab[1] * sba[1];
-          const1 += pb.occ[k * nb + a] / nk * pb.occ[k * nb + b] * c1a * re / (pb.omega * pb.omega);
+          const double fab = pb.occ[k * nb + a] / nk * pb.occ[k * nb + b] * c1a / (pb.omega * pb.omega);
+          const1 += fab * re;
+          if (bitc) const1i += fab * (sab[0] * sba[1] + sab[1] * sba[0]);
         }
     hipLaunchKernelGGL(k_corr_apply, dim3(nblk(long(P) * pb.npw_max)), dim3(256), 0, s, sh.coef.p, sh.S.p, sh.O.p,
                        sh.Zg.p, sh.Wg.p, focc.p, sh.npw.p, nb, pb.npw_max, P, pb.omega, m.m2ax, pb.delta_gb, m.m3a2,
-                       const1, m.m3b6, c1s * n0, sh.dhc2.p, sh.dhc3.p);
-    hipLaunchKernelGGL(k_corr_add, dim3(P), dim3(256), 0, s, sh.coef.p, sh.dhc2.p, sh.dhc3.p, sh.npw.p, nb,
-                       pb.npw_max, sh.out.p, sh.ecorr.p);
+                       const1, const1i, m.m3b6, c1s * n0, c1s * n0i, sh.dhc2.p, sh.dhc3.p);
+    hipLaunchKernelGGL(k_corr_add, dim3(P), dim3(256), 0, s, cl, sh.dhc2.p, sh.dhc3.p, sh.npw.p, nb, pb.npw_max,
+                       sh.out.p, sh.ecorr.p);
   }
 };
 
@@ -1180,8 +1403,14 @@ int prepare(tc_ctx* c) {
   if (pb.N == 0) return fail(c, TC_ERR_STATE, "tc_set_grid not called");
   if (!pb.jastrow) return fail(c, TC_ERR_STATE, "tc_set_jastrow not called");
   if (pb.nb == 0) return fail(c, TC_ERR_STATE, "no orbitals loaded");
-  for (int k = 0; k < pb.nk; ++k)
+  int nleft = 0;
+  for (int k = 0; k < pb.nk; ++k) {
     if (!pb.loaded[k]) return fail(c, TC_ERR_STATE, "orbitals of k-point " + std::to_string(k) + " not loaded");
+    nleft += pb.left[k];
+  }
+  if (nleft != 0 && nleft != pb.nk)
+    return fail(c, TC_ERR_STATE, "left orbitals are loaded for some k-points only");
+  pb.bitc = nleft == pb.nk;
   if (!c->eng || c->eng_prec != pb.prec || c->eng_N != pb.N) {
     if (pb.prec == TC_PREC_FP32_SPLITBF16 && pb.N % 8 != 0)
       return fail(c, TC_ERR_UNSUPPORTED, "split-BF16 DFT stages need a grid length divisible by 8");
@@ -1286,6 +1515,7 @@ int do_backward(tc_ctx* c, void* grad_dev, double* grad_host, double* dA, double
     return fail(c, TC_ERR_UNSUPPORTED, "the gradient of the grad-u . grad terms needs 2ah and 2ax selected");
   int st = prepare(c);
   if (st != TC_OK) return st;
+  if (pb.bitc) return fail(c, TC_ERR_UNSUPPORTED, "the gradient is built for TC mode (no left orbitals)");
   struct Keep {
     tc_ctx* c;
     uint64_t mask;
@@ -1382,12 +1612,44 @@ int begin_load(tc_ctx* c, int ik, int nband, const double* occ) {
     pb.nb = nband;
     pb.occ.assign(size_t(pb.nk) * nband, 0.0);
     std::fill(pb.loaded.begin(), pb.loaded.end(), 0);
+    std::fill(pb.left.begin(), pb.left.end(), 0);
   }
   int mx = 0;
   for (int k = 0; k < pb.nk; ++k) mx = std::max(mx, pb.npw[k]);
   pb.npw_max = mx;
   c->sh.coef.alloc(size_t(2) * pb.P() * pb.npw_max);
   for (int b = 0; b < nband; ++b) pb.occ[size_t(ik) * nband + b] = occ[b];
+  return TC_OK;
+}
+
+// FP64 biorthogonalisation of k-point ik on the device (see k_bo_normalize / k_bo_invert / k_bo_left):
+// the right coefficients in sh.coef are normalised in place, the left ones (staged in sh.bo_l) are
+// written to sh.coefL.
+int biorthogonalize(tc_ctx* c, int ik) {
+  Problem& pb = c->pb;
+  Shared& sh = c->sh;
+  const int nb = pb.nb, npw = pb.npw[ik], npm = pb.npw_max;
+  const size_t off = size_t(2) * ik * nb * npm;
+  sh.coefL.alloc(size_t(2) * pb.P() * npm);
+  sh.bo_s.alloc(size_t(2) * nb * nb);
+  sh.bo_inv.alloc(size_t(2) * nb * nb);
+  sh.bo_aug.alloc(size_t(2) * (size_t(nb) * 2 * nb + nb));
+  sh.bo_flag.alloc(1);
+  hipStream_t s = c->stream;
+  TC_HIP(hipMemsetAsync(sh.bo_flag.p, 0, sizeof(int), s));
+  hipLaunchKernelGGL(k_bo_normalize, dim3(nb), dim3(256), 0, s, sh.coef.p + off, npw, npm, sh.bo_flag.p);
+  hipLaunchKernelGGL(k_overlap, dim3(nb * nb), dim3(256), 0, s, sh.bo_l.p, sh.coef.p + off, sh.npw.p + ik, nb, npm, 1,
+                     sh.bo_s.p);
+  hipLaunchKernelGGL(k_bo_invert, dim3(1), dim3(256), 0, s, sh.bo_s.p, nb, sh.bo_aug.p, sh.bo_inv.p, sh.bo_flag.p);
+  int flag = 0;
+  TC_HIP(hipMemcpyAsync(&flag, sh.bo_flag.p, sizeof(int), hipMemcpyDeviceToHost, s));
+  TC_HIP(hipStreamSynchronize(s));
+  if (flag == 1) return fail(c, TC_ERR_ARG, "a right orbital of k-point " + std::to_string(ik) + " is zero");
+  if (flag == 2)
+    return fail(c, TC_ERR_ARG, "the left/right overlap of k-point " + std::to_string(ik) + " is singular");
+  hipLaunchKernelGGL(k_bo_left, dim3(nblk(long(nb) * npm)), dim3(256), 0, s, sh.bo_inv.p, sh.bo_l.p, nb, npw, npm,
+                     sh.coefL.p + off);
+  TC_HIP(hipStreamSynchronize(s));
   return TC_OK;
 }
 
@@ -1468,6 +1730,7 @@ int tc_set_kmesh(tc_ctx* c, int n1, int n2, int n3) {
     pb.miller.assign(pb.nk, {});
     pb.npw.assign(pb.nk, 0);
     pb.loaded.assign(pb.nk, 0);
+    pb.left.assign(pb.nk, 0);
     pb.nb = 0;
     c->tables_dirty = true;
     c->have_result = false;
@@ -1537,20 +1800,32 @@ int tc_set_options(tc_ctx* c, int precision, double alpha, int div_correction, u
 
 int tc_load_orbitals(tc_ctx* c, int ik, int nband, const double* right, const double* left, const double* occ) {
   return guard(c, [&]() -> int {
-    if (left) return fail(c, TC_ERR_UNSUPPORTED, "biorthogonal (left) orbitals are not built in this version");
     if (!right) return fail(c, TC_ERR_ARG, "null coefficients");
     int st = begin_load(c, ik, nband, occ);
     if (st != TC_OK) return st;
     Problem& pb = c->pb;
     const int npw = pb.npw[ik];
+    pb.loaded[ik] = 0;
+    pb.left[ik] = 0;
+    c->have_result = false;
     std::vector<double> stage(size_t(2) * nband * pb.npw_max, 0.0);
-    for (int b = 0; b < nband; ++b)
-      std::memcpy(&stage[size_t(2) * b * pb.npw_max], right + size_t(2) * b * npw, size_t(2) * npw * sizeof(double));
+    auto pack = [&](const double* src) {
+      for (int b = 0; b < nband; ++b)
+        std::memcpy(&stage[size_t(2) * b * pb.npw_max], src + size_t(2) * b * npw, size_t(2) * npw * sizeof(double));
+    };
+    pack(right);
     TC_HIP(hipMemcpy(c->sh.coef.p + size_t(2) * ik * nband * pb.npw_max, stage.data(), stage.size() * sizeof(double),
                      hipMemcpyHostToDevice));
-    pb.loaded[ik] = 1;
     upload_basis_data(c);
-    c->have_result = false;
+    if (left) {
+      pack(left);
+      c->sh.bo_l.alloc(stage.size());
+      TC_HIP(hipMemcpy(c->sh.bo_l.p, stage.data(), stage.size() * sizeof(double), hipMemcpyHostToDevice));
+      st = biorthogonalize(c, ik);
+      if (st != TC_OK) return st;
+      pb.left[ik] = 1;
+    }
+    pb.loaded[ik] = 1;
     return TC_OK;
   });
 }
@@ -1568,6 +1843,7 @@ int tc_load_orbitals_dev(tc_ctx* c, int ik, int nband, const void* right_dev, co
                             size_t(2) * npw * sizeof(double), nband, hipMemcpyDeviceToDevice, c->stream));
     TC_HIP(hipStreamSynchronize(c->stream));
     pb.loaded[ik] = 1;
+    pb.left[ik] = 0;
     upload_basis_data(c);
     c->have_result = false;
     return TC_OK;

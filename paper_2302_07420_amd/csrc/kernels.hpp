@@ -156,18 +156,27 @@ __global__ void k_gather(const cx<R>* f, const int* boxidx, const int* npw, int 
   out[2 * (long(j) * npw_max + g) + 1] = im;
 }
 
-// ---------------------------------------------------------------- densities (TC: chi = phi)
-// n = sum_q w_q |psi_q|^2, J_c = sum_q w_q conj(psi_q) D_qc, accumulated in FP64.
+// ---------------------------------------------------------------- densities
+// n = sum_q w_q conj(chi_q) psi_q, J_c = sum_q w_q conj(chi_q) D_qc, accumulated in FP64 (Sec. 2.6.3;
+// TC mode: chi = psi, the same array, and n is real).
 template <typename R, int N>
-__global__ void k_density(const cx<R>* psi, const cx<R>* D, const double* w, int P, cx<R>* n, cx<R>* J) {
+__global__ void k_density(const cx<R>* chi, const cx<R>* psi, const cx<R>* D, const double* w, int P, cx<R>* n,
+                          cx<R>* J) {
   constexpr long NR = long(N) * N * N;
   const long r = long(blockIdx.x) * blockDim.x + threadIdx.x;
   if (r >= NR) return;
-  double nn = 0, jr[3] = {0, 0, 0}, ji[3] = {0, 0, 0};
+  const bool tc = chi == psi;
+  double nn = 0, ni = 0, jr[3] = {0, 0, 0}, ji[3] = {0, 0, 0};
   for (int q = 0; q < P; ++q) {
-    const cx<R> a = psi[q * NR + r];
+    const cx<R> a = chi[q * NR + r];
     const double wq = w[q];
-    nn += wq * (double(a.x) * a.x + double(a.y) * a.y);
+    if (tc) {
+      nn += wq * (double(a.x) * a.x + double(a.y) * a.y);
+    } else {
+      const cx<R> b = psi[q * NR + r];
+      nn += wq * (double(a.x) * b.x + double(a.y) * b.y);
+      ni += wq * (double(a.x) * b.y - double(a.y) * b.x);
+    }
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       const cx<R> d = D[(long(c) * P + q) * NR + r];
@@ -175,7 +184,7 @@ __global__ void k_density(const cx<R>* psi, const cx<R>* D, const double* w, int
       ji[c] += wq * (double(a.x) * d.y - double(a.y) * d.x);
     }
   }
-  n[r] = mk<R>(R(nn), R(0));
+  n[r] = mk<R>(R(nn), R(ni));
 #pragma unroll
   for (int c = 0; c < 3; ++c) J[c * NR + r] = mk<R>(R(jr[c]), R(ji[c]));
 }
@@ -406,22 +415,26 @@ struct PlaneWG {
   }
 };
 
-// Pair densities rho = conj(psi_a) psi_b, forward xy transformed, for the pairs (t, q) of a target
-// batch: TFIRST (occupied pass) a = t0 + t, b = q; else a = q, b = t0 + t.  out[(t P + q)][N^3].
+// Pair densities rho = conj(bra_a) ket_b, forward xy transformed, for the pairs (t, q) of a target
+// batch: TFIRST a = t0 + t, b = q; else a = q, b = t0 + t.  out[(t P + q)][N^3].  bra holds the left
+// orbitals chi (the right ones, psi, in TC mode), ket the right ones.
 template <typename R, int N, bool TFIRST>
-__global__ void __launch_bounds__((Fz<R, N>::NTH)) k_pair_xy(const cx<R>* psi, FusedArgs fa, cx<R>* out) {
+__global__ void __launch_bounds__((Fz<R, N>::NTH)) k_pair_xy(const cx<R>* bra, const cx<R>* ket, FusedArgs fa,
+                                                           cx<R>* out) {
   using F = Fz<R, N>;
   constexpr int KP = F::KP, RB = F::RB;
   constexpr long NR = long(N) * N * N;
   __shared__ cx<R> sm[F::GRP * F::PLANE];
   const PlaneWG<R, N> wg(fa);
+  const cx<R>* tf = TFIRST ? bra : ket;   // field of the target index
+  const cx<R>* pf = TFIRST ? ket : bra;   // field of the partner index
   cx<R> pt[KP];
 #pragma unroll
-  for (int i = 0; i < KP; ++i) pt[i] = psi[long(fa.t0 + wg.t) * NR + wg.zo + RB * N * i];
+  for (int i = 0; i < KP; ++i) pt[i] = tf[long(fa.t0 + wg.t) * NR + wg.zo + RB * N * i];
   for (int q0 = wg.qb; q0 < wg.qe; q0 += F::GRP) {
     const int nq = min(F::GRP, wg.qe - q0);
     for (int cc = 0; cc < nq; ++cc) {
-      const cx<R>* pq = psi + long(q0 + cc) * NR + wg.zo;
+      const cx<R>* pq = pf + long(q0 + cc) * NR + wg.zo;
 #pragma unroll
       for (int i = 0; i < KP; ++i)
         sm[cc * F::PLANE + wg.so0 + RB * F::LD * i] = TFIRST ? cmulc(pt[i], pq[RB * N * i]) : cmulc(pq[RB * N * i], pt[i]);
@@ -437,18 +450,18 @@ __global__ void __launch_bounds__((Fz<R, N>::NTH)) k_pair_xy(const cx<R>* psi, F
   }
 }
 
-// Pass-B sources of the pairs (t, q), in lattice components: T_d = conj(psi_q) Zl_td +
-// m3b5 conj(Hl_qd) psi_t, with Zl = B (m2bx2 D_j - m3b3 h1 psi_j + m3b4 h4_j) and Hl = B H3a4 (TC mode:
-// H3b = conj(H3a4)); forward xy transformed: out[(pair 2 + 0)] = kappa_1 T~_1 + kappa_2 T~_2,
-// out[(pair 2 + 1)] = T~_3, pair = t P + q, Delta = k_t - k_q.
+// Pass-B sources of the pairs (t, q), in lattice components: T_d = conj(chi_q) Zl_td +
+// m3b5 conj(Hl_qd) psi_t, with Zl = B (m2bx2 D_j - m3b3 h1 psi_j + m3b4 h4_j) and Hl = B conj(H3b)
+// (TC mode: chi = psi and H3b = conj(H3a4), so Hl = B H3a4); forward xy transformed:
+// out[(pair 2 + 0)] = kappa_1 T~_1 + kappa_2 T~_2, out[(pair 2 + 1)] = T~_3, pair = t P + q, Delta = k_t - k_q.
 // occupancy target: 3 waves per SIMD where that costs no spills (FP32 at 24^3)
 template <typename R, int N>
 constexpr int kPassBWaves = (sizeof(R) == 4 && N == 24) ? 3 : 1;
 
 template <typename R, int N>
 __global__ void __launch_bounds__((Fz<R, N>::NTH)) __attribute__((amdgpu_waves_per_eu(kPassBWaves<R, N>)))
-k_passB_xy(const cx<R>* psi, const cx<R>* Zl, const cx<R>* Hl, FusedArgs fa, MeshInfo mi, const double* dfr,
-           R m3b5, cx<R>* out) {
+k_passB_xy(const cx<R>* psi, const cx<R>* chi, const cx<R>* Zl, const cx<R>* Hl, FusedArgs fa, MeshInfo mi,
+           const double* dfr, R m3b5, cx<R>* out) {
   using F = Fz<R, N>;
   constexpr int KP = F::KP, RB = F::RB;
   constexpr int NPQ = F::GRP / 3 < 1 ? 1 : F::GRP / 3;   // partners per LDS round (three planes each)
@@ -468,13 +481,13 @@ k_passB_xy(const cx<R>* psi, const cx<R>* Zl, const cx<R>* Hl, FusedArgs fa, Mes
       for (int d = 0; d < 3; ++d) zt[i][d] = zb[d * NR + r];
     }
   }
-  // partner fields psi_q, Hl_q of the next round are loaded while this round is transformed
+  // partner fields chi_q, Hl_q of the next round are loaded while this round is transformed
   cx<R> pre[NPQ][4][KP];
   auto fetch = [&](int q0) {
 #pragma unroll
     for (int a = 0; a < NPQ; ++a) {
       const int q = min(q0 + a, wg.qe - 1);
-      const cx<R>* pq = psi + long(q) * NR;
+      const cx<R>* pq = chi + long(q) * NR;
       const cx<R>* hq = Hl + long(q) * 3 * NR;
 #pragma unroll
       for (int i = 0; i < KP; ++i) {
@@ -1122,6 +1135,143 @@ __global__ void __launch_bounds__((Fz<R, N>::NTH)) k_fused_O(const cx<R>* buf4, 
   }
 }
 
+// Occupied-occupied pass with left orbitals (biorthogonal mode), a = t0 + t (q2 of Algs. 3a2, 3a4, 3b2),
+// b = q (q1).  V21 comes from rho21 = conj(chi_a) psi_b (Delta = k_b - k_a, buf21) and V12 from
+// rho12 = conj(chi_b) psi_a (Delta = k_a - k_b, buf12); each holds [W0_par, W3_par, W0_anti, W3_anti] per
+// pair, xy in G space.  With V the Cartesian vector fields:
+//   h5[a]  += w_b sum_s V21_s . V12_s        (Alg. 3a2, bilinear; complex)
+//   H3a4[a] += w_b V12_par psi_b              (Alg. 3a4 h3)
+//   H3bc[a] += w_b conj(V21_par) chi_b        (conjugate of the h3 of Algs. 3b2 / 3b5)
+template <typename R, int N>
+struct PassOB {
+  static constexpr bool SPLIT = !Fz<R, N>::fits(6);   // V21 and V12 in separate LDS rounds
+  static constexpr int NPL = SPLIT ? 3 : 6;
+};
+
+template <typename R, int N>
+__global__ void __launch_bounds__((Fz<R, N>::NTH)) k_fused_OB(const cx<R>* buf21, const cx<R>* buf12,
+                                                            const cx<R>* psi, const cx<R>* chi, const double* w,
+                                                            FusedArgs fa, MeshInfo mi, Recip rc, const double* dfr,
+                                                            cx<R>* h5part, cx<R>* H3part, cx<R>* Hbpart) {
+  using F = Fz<R, N>;
+  constexpr int KP = F::KP, RB = F::RB, PL = F::PLANE;
+  constexpr bool SPLIT = PassOB<R, N>::SPLIT;
+  constexpr long NR = long(N) * N * N;
+  __shared__ cx<R> sm[PassOB<R, N>::NPL * PL];
+  const PlaneWG<R, N> wg(fa);
+  const Basis<R> B = basis<R>(rc);
+  const int ja = fa.t0 + wg.t;
+  cx<R> h5[KP], H[KP][3], Hb[KP][3], X21[KP][3];
+#pragma unroll
+  for (int i = 0; i < KP; ++i) {
+    h5[i] = mk<R>(R(0), R(0));
+#pragma unroll
+    for (int c = 0; c < 3; ++c) H[i][c] = Hb[i][c] = mk<R>(R(0), R(0));
+  }
+  for (int q = wg.qb; q < wg.qe; ++q) {
+    const R wq = R(w[q]);
+    const long pair = long(wg.t) * fa.P + q;
+    const double* del[2] = {dfr + 3 * pair_dindex(mi, ja, q, 0), dfr + 3 * pair_dindex(mi, ja, q, 1)};
+    const cx<R>* src[2] = {buf21 + pair * 4 * NR + wg.zo, buf12 + pair * 4 * NR + wg.zo};
+#pragma unroll 1
+    for (int ch = 0; ch < 2; ++ch) {   // spin channel of the kernel: parallel, antiparallel
+#pragma unroll 1
+      for (int h = 0; h < (SPLIT ? 2 : 1); ++h) {
+        // LDS rounds: unsplit, slots 0-2 V21 and 3-5 V12; split, round h holds field h in slots 0-2
+#pragma unroll
+        for (int v = 0; v < 2; ++v) {
+          if (SPLIT && v != h) continue;
+          const int base = SPLIT ? 0 : 3 * v;
+          const R k1 = R(double(mfreq<N>(wg.x)) + del[v][0]);
+#pragma unroll
+          for (int i = 0; i < KP; ++i) {
+            const int so = wg.so0 + RB * F::LD * i;
+            const long o = RB * N * i;
+            const R k2 = R(double(mfreq<N>(wg.y0 + RB * i)) + del[v][1]);
+            const cx<R> w0 = src[v][(2 * ch) * NR + o];
+            sm[base * PL + so] = mul_i(k1 * w0);
+            sm[(base + 1) * PL + so] = mul_i(k2 * w0);
+            sm[(base + 2) * PL + so] = src[v][(2 * ch + 1) * NR + o];
+          }
+        }
+        __syncthreads();
+        planes_fft<R, N, 1>(sm, SPLIT ? 3 : 6, threadIdx.x);
+#pragma unroll
+        for (int i = 0; i < KP; ++i) {
+          const long r = wg.zo + RB * N * i;
+          const int so = wg.so0 + RB * F::LD * i;
+          cx<R> Y[3], X12[3];
+          if (!SPLIT || h == 0) {
+#pragma unroll
+            for (int d = 0; d < 3; ++d) Y[d] = sm[d * PL + so];
+            to_cart(B, Y, X21[i]);
+          }
+          if (!SPLIT || h == 1) {
+            const int base = SPLIT ? 0 : 3;
+#pragma unroll
+            for (int d = 0; d < 3; ++d) Y[d] = sm[(base + d) * PL + so];
+            to_cart(B, Y, X12);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) h5[i] = h5[i] + wq * (X21[i][c] * X12[c]);
+            if (ch == 0) {
+              const cx<R> pb = psi[long(q) * NR + r], xb = chi[long(q) * NR + r];
+#pragma unroll
+              for (int c = 0; c < 3; ++c) {
+                H[i][c] = H[i][c] + wq * (X12[c] * pb);
+                Hb[i][c] = Hb[i][c] + wq * cmulc(X21[i][c], xb);
+              }
+            }
+          }
+        }
+        __syncthreads();
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < KP; ++i) {
+    const long r = wg.zo + RB * N * i;
+    const long o = long(wg.c) * fa.T + wg.t;
+    h5part[o * NR + r] = h5[i];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      H3part[(o * 3 + c) * NR + r] = H[i][c];
+      Hbpart[(o * 3 + c) * NR + r] = Hb[i][c];
+    }
+  }
+}
+
+// Fixed-order FP64 sums of the partials of k_fused_OB: h5[t0+t], H3a4[t0+t], H3bc[t0+t].
+template <typename R, int N>
+__global__ void k_sum_parts_ob(int S, int T, int t0, const cx<R>* h5part, const cx<R>* H3part,
+                               const cx<R>* Hbpart, cx<R>* h5, cx<R>* H3a4, cx<R>* H3bc) {
+  constexpr long NR = long(N) * N * N;
+  const long id = long(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (id >= long(T) * NR) return;
+  const int t = int(id / NR);
+  const long r = id - long(t) * NR;
+  cx<double> s = {0, 0}, H[3] = {{0, 0}, {0, 0}, {0, 0}}, Hb[3] = {{0, 0}, {0, 0}, {0, 0}};
+  for (int c = 0; c < S; ++c) {
+    const long o = long(c) * T + t;
+    const cx<R> v = h5part[o * NR + r];
+    s.x += double(v.x);
+    s.y += double(v.y);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const cx<R> a = H3part[(o * 3 + d) * NR + r], b = Hbpart[(o * 3 + d) * NR + r];
+      H[d].x += double(a.x);
+      H[d].y += double(a.y);
+      Hb[d].x += double(b.x);
+      Hb[d].y += double(b.y);
+    }
+  }
+  h5[long(t0 + t) * NR + r] = mk<R>(R(s.x), R(s.y));
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    H3a4[(long(t0 + t) * 3 + d) * NR + r] = mk<R>(R(H[d].x), R(H[d].y));
+    H3bc[(long(t0 + t) * 3 + d) * NR + r] = mk<R>(R(Hb[d].x), R(Hb[d].y));
+  }
+}
+
 // Sum of the partner-chunk partials in a fixed order (FP64).
 //   mode 0 (occ): h5[t0+t] = sum_c h5part, H3a4[t0+t] = sum_c H3part                  (working precision)
 //   mode 1 (A)  : acc[s][t] += sum_c gpart[c][t][s] (s = 0,1,2), h4[t] = sum_c h4part
@@ -1241,25 +1391,37 @@ __global__ void __launch_bounds__(256) k_epart(const cx<R>* psi, const cx<double
   if (threadIdx.x == 0) e[long(t0 + t) * 4 + slot] = red[0] / double(NR);
 }
 
-// h6 = sum_a w_a h5[a];  M_c = sum_a w_a conj(H3a4[a]_c) psi_a  (H3b = conj(H3a4) in TC mode)
-template <typename R, int N>
-__global__ void k_reduce_occ(const R* h5, const cx<R>* H3a4, const cx<R>* psi, const double* w, int P, cx<R>* h6,
+// h6 = sum_a w_a h5[a];  M_c = sum_a w_a conj(H3c[a]_c) psi_a, H3c = conj(H3b) (Alg. 3b2 source;
+// TC mode: H3c = H3a4 and h5 real)
+__device__ __forceinline__ double re_part(float v) { return v; }
+__device__ __forceinline__ double re_part(double v) { return v; }
+__device__ __forceinline__ double im_part(float) { return 0.0; }
+__device__ __forceinline__ double im_part(double) { return 0.0; }
+template <typename R>
+__device__ __forceinline__ double re_part(cx<R> v) { return double(v.x); }
+template <typename R>
+__device__ __forceinline__ double im_part(cx<R> v) { return double(v.y); }
+
+template <typename R, int N, typename H5>
+__global__ void k_reduce_occ(const H5* h5, const cx<R>* H3c, const cx<R>* psi, const double* w, int P, cx<R>* h6,
                              cx<R>* M) {
   constexpr long NR = long(N) * N * N;
   const long r = long(blockIdx.x) * blockDim.x + threadIdx.x;
   if (r >= NR) return;
-  double s = 0, mr[3] = {0, 0, 0}, mi[3] = {0, 0, 0};
+  double s = 0, si = 0, mr[3] = {0, 0, 0}, mi[3] = {0, 0, 0};
   for (int a = 0; a < P; ++a) {
-    s += w[a] * double(h5[long(a) * NR + r]);
+    const H5 hv = h5[long(a) * NR + r];
+    s += w[a] * re_part(hv);
+    si += w[a] * im_part(hv);
     const cx<R> pa = psi[long(a) * NR + r];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      const cx<R> v = cmulc(H3a4[(long(a) * 3 + c) * NR + r], pa);
+      const cx<R> v = cmulc(H3c[(long(a) * 3 + c) * NR + r], pa);
       mr[c] += w[a] * double(v.x);
       mi[c] += w[a] * double(v.y);
     }
   }
-  h6[r] = mk<R>(R(s), R(0));
+  h6[r] = mk<R>(R(s), R(si));
 #pragma unroll
   for (int c = 0; c < 3; ++c) M[c * NR + r] = mk<R>(R(mr[c]), R(mi[c]));
 }

@@ -233,6 +233,9 @@ WORKLOADS = {
     "heg54_twist2_g32": heg_twist,
     # 2x2x2 supercell of the fcc cell, 2x2x2 k-mesh, 32 bands, ~2400 plane waves, 48^3 grid (65,536 pairs)
     "fcc_si_x2_k222_g48": lambda: fcc_si(kmesh=(2, 2, 2), grid=48, nb=32, supercell=2, seed_offset=4),
+    # the fcc bench shape in the biorthogonal mode: left orbitals chi = phi + 0.1 z (z random, same
+    # envelope, unit norm), biorthogonalised by the consumer
+    "fcc_si_k444_g24_bitc": lambda: fcc_si(left_mix=0.1).replace(name="fcc_si_x1_k4x4x4_g24_bitc"),
 }
 
 

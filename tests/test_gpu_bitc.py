@@ -1,0 +1,191 @@
+"""Biorthogonal (BITC) mode of the HIP path through the C ABI: left orbitals chi != phi.
+
+Small cases: every term and the total against the FP64 oracle, which biorthogonalises
+the same inputs (Sec. 2.3) and evaluates every chi* in place of phi* (Eq. BITCSCF).
+Independent of the oracle: left = M right (any invertible M per k) must reproduce TC
+mode exactly, since the biorthogonalised left set then equals the right one.
+Full bench shape: FP32 (the benchmark's precision) and split BF16 against FP64, and
+sampled targets against the oracle restricted to them.
+"""
+import numpy as np
+import pytest
+
+import tcinputs as T
+from oracle.fftroute import ALL_TERMS, MULT, Problem
+
+pytestmark = pytest.mark.gpu
+
+tc = pytest.importorskip("paper_2302_07420_amd")
+
+FP64_TOL = 1e-10
+FP32_TOL = 2e-6
+SPLIT_TOL = 2e-5
+PAIR_FREE = ("2ah", "2bh1", "2bh2", "2ax", "2bx1", "2bx2", "3a1", "3a3", "3b1", "3b3", "3b4", "3b6")
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def relerr(a, b):
+    scale = max(np.abs(x).max() for x in b)
+    return max(np.abs(x - y).max() for x, y in zip(a, b)) / scale
+
+
+CASES = {
+    "fcc_k211_g8_bitc": lambda: T.tiny_fcc(kmesh=(2, 1, 1), grid=8, ecut=2.0, nb=2, a=6.0, occ=[1.0, 0.7],
+                                           left_mix=0.15),
+    "fcc_k221_g12_bitc_empty_band": lambda: T.tiny_fcc(kmesh=(2, 2, 1), grid=12, ecut=2.0, nb=3, a=6.0,
+                                                       occ=[1.0, 0.8, 0.0], left_mix=0.2, seed_offset=7),
+    "fcc_k121_g16_bitc": lambda: T.tiny_fcc(kmesh=(1, 2, 1), grid=16, ecut=3.0, nb=2, a=7.0, left_mix=0.1,
+                                            seed_offset=9),
+}
+
+
+@pytest.fixture(scope="module", params=list(CASES))
+def case(request):
+    w = CASES[request.param]()
+    pr = Problem(w)
+    assert pr.cl is not None
+    per = {t: [c.numpy() for c in pr.to_coeff(MULT.get(t, 1) * pr.term(t, 0))] for t in ALL_TERMS}
+    tot = [sum(per[t][k] for t in ALL_TERMS) for k in range(w.nk)]
+    return request.param, w, per, tot, float(pr.energy())
+
+
+def test_every_term_fp64(case):
+    name, w, per, tot, E = case
+    scale = max(np.abs(x).max() for x in tot)
+    for t in ALL_TERMS:
+        _say(f"[gpu] bitc {name} fp64 term {t}")
+        op = tc.from_workload(w, precision=tc.TC_PREC_FP64, terms=tc.TERM_BITS[t] | tc.TERM_BITS["corr"])
+        hc = op.apply()
+        op.close()
+        err = max(np.abs(h - r).max() for h, r in zip(hc, per[t])) / scale
+        assert err < FP64_TOL, (t, err)
+
+
+@pytest.mark.parametrize("batch", [0, 1])
+def test_total_and_energy_fp64(case, batch):
+    name, w, per, tot, E = case
+    _say(f"[gpu] bitc {name} fp64 all terms batch={batch}")
+    op = tc.from_workload(w, precision=tc.TC_PREC_FP64, batch=batch)
+    hc = op.apply()
+    Eg, _ = op.energy()
+    op.close()
+    err = relerr(hc, tot)
+    _say(f"    element error {err:.3e}, energy {Eg!r} vs {E!r}")
+    assert err < FP64_TOL
+    assert abs(Eg - E) < FP64_TOL * abs(E)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "split"])
+def test_total_and_energy_reduced(case, prec):
+    name, w, per, tot, E = case
+    if prec == "split" and w.grid[0] % 8:
+        pytest.skip("split-BF16 z stage needs a grid length divisible by 8")
+    _say(f"[gpu] bitc {name} {prec} all terms")
+    p = tc.TC_PREC_FP32 if prec == "fp32" else tc.TC_PREC_FP32_SPLITBF16
+    op = tc.from_workload(w, precision=p, batch=2)
+    hc = op.apply()
+    Eg, _ = op.energy()
+    op.close()
+    err = relerr(hc, tot)
+    _say(f"    element error {err:.3e}, energy error {abs(Eg - E) / abs(E):.3e}")
+    assert err < (FP32_TOL if prec == "fp32" else SPLIT_TOL)
+    assert abs(Eg - E) < 1e-6 * abs(E)
+
+
+def test_left_in_span_of_right_equals_tc():
+    """left = M right: the biorthogonalised left set is the right set, so BITC = TC (no oracle)."""
+    w = T.tiny_fcc(kmesh=(2, 2, 1), grid=12, ecut=2.0, nb=3, a=6.0, occ=[1.0, 0.9, 0.4], seed_offset=21)
+    rng = np.random.default_rng(5)
+    left = []
+    for c in w.right:
+        nb = c.shape[0]
+        M = np.eye(nb) + 0.4 * (rng.standard_normal((nb, nb)) + 1j * rng.standard_normal((nb, nb)))
+        left.append(M @ c)
+    _say("[gpu] bitc left = M right vs TC, fp64")
+    op = tc.from_workload(w, precision=tc.TC_PREC_FP64)
+    h_tc = op.apply()
+    E_tc = op.energy()
+    op.close()
+    op = tc.from_workload(w, precision=tc.TC_PREC_FP64, left=left)
+    h_bi = op.apply()
+    E_bi = op.energy()
+    op.close()
+    err = relerr(h_bi, h_tc)
+    _say(f"    element difference {err:.3e}; energies {E_bi[0]!r} {E_tc[0]!r}")
+    assert err < 1e-11
+    assert abs(E_bi[0] - E_tc[0]) < 1e-12 * abs(E_tc[0])
+    for k in E_tc[1]:
+        assert E_bi[1][k] == pytest.approx(E_tc[1][k], rel=1e-11, abs=1e-13), k
+
+
+def test_error_paths():
+    w = CASES["fcc_k211_g8_bitc"]()
+    _say("[gpu] bitc error paths")
+    op = tc.from_workload(w, precision=tc.TC_PREC_FP64)
+    with pytest.raises(tc.TCError, match="status -5"):       # gradient is TC-only
+        op.backward()
+    op.load_orbitals(1, w.right[1], w.occ[1])                 # k-point 1 back to TC: mixed modes
+    with pytest.raises(tc.TCError, match="status -2"):
+        op.apply()
+    with pytest.raises(tc.TCError, match="status -1"):       # singular overlap
+        op.load_orbitals(0, w.right[0], w.occ[0], left=np.zeros_like(w.left[0]))
+    with pytest.raises(tc.TCError, match="status -1"):       # zero right orbital
+        r = w.right[0].copy()
+        r[1] = 0
+        op.load_orbitals(0, r, w.occ[0], left=w.left[0])
+    op.load_orbitals(0, w.right[0], w.occ[0], left=w.left[0])
+    op.load_orbitals(1, w.right[1], w.occ[1], left=w.left[1])
+    hc = op.apply()                                           # recovers after the failed loads
+    op.close()
+    pr = Problem(w)
+    tot = [c.numpy() for c in pr.to_coeff(sum(MULT.get(t, 1) * pr.term(t, 0) for t in ALL_TERMS))]
+    assert relerr(hc, tot) < FP64_TOL
+
+
+@pytest.fixture(scope="module")
+def bench_bitc():
+    w = T.workload("fcc_si_k444_g24_bitc")
+    out = {}
+    for name, prec in (("fp64", tc.TC_PREC_FP64), ("fp32", tc.TC_PREC_FP32), ("split", tc.TC_PREC_FP32_SPLITBF16)):
+        _say(f"[gpu] bitc fcc_si_k444_g24 {name}")
+        op = tc.from_workload(w, precision=prec)
+        out[name] = (op.apply(), op.energy()[0])
+        op.close()
+    return w, out
+
+
+@pytest.mark.parametrize("prec,tol", [("fp32", FP32_TOL), ("split", SPLIT_TOL)])
+def test_bench_shape_reduced_vs_fp64(bench_bitc, prec, tol):
+    w, out = bench_bitc
+    err = relerr(out[prec][0], out["fp64"][0])
+    de = abs(out[prec][1] - out["fp64"][1]) / abs(out["fp64"][1])
+    _say(f"    bitc {prec} vs fp64: element difference {err:.3e}, energy {de:.3e}")
+    assert err < tol
+    assert de < 1e-6
+
+
+def test_bench_shape_sampled_targets_fp64(bench_bitc):
+    w, out = bench_bitc
+    targets = [0, 149, 255]
+    _say(f"[gpu] bitc fcc_si_k444_g24 fp64: sampled targets {targets} vs oracle (pair-free terms)")
+    pr = Problem(w)
+    pr.restrict_targets(targets)
+    ref = 0
+    for t in PAIR_FREE:
+        ref = ref + MULT.get(t, 1) * pr.term(t, 0)
+    exp = pr.to_coeff(ref)
+    nb = w.right[0].shape[0]
+    exp_rows = [exp[j // nb][j % nb].numpy() for j in targets]
+    mask = 0
+    for t in PAIR_FREE:
+        mask |= tc.TERM_BITS[t]
+    op = tc.from_workload(w, precision=tc.TC_PREC_FP64, terms=mask | tc.TERM_BITS["corr"])
+    hc = op.apply()
+    op.close()
+    got = [hc[j // nb][j % nb] for j in targets]
+    err = relerr(got, exp_rows)
+    _say(f"    max element error / max |h c| = {err:.3e}")
+    assert err < FP64_TOL
