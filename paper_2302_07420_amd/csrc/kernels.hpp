@@ -1146,6 +1146,8 @@ template <typename R, int N>
 struct PassOB {
   static constexpr bool SPLIT = !Fz<R, N>::fits(6);   // V21 and V12 in separate LDS rounds
   static constexpr int NPL = SPLIT ? 3 : 6;
+  // register prefetch of the next round where it costs no spills (FP32 up to 32 points)
+  static constexpr bool PF = sizeof(R) == 4 && N <= 32;
 };
 
 template <typename R, int N>
@@ -1155,7 +1157,7 @@ __global__ void __launch_bounds__((Fz<R, N>::NTH)) k_fused_OB(const cx<R>* buf21
                                                             cx<R>* h5part, cx<R>* H3part, cx<R>* Hbpart) {
   using F = Fz<R, N>;
   constexpr int KP = F::KP, RB = F::RB, PL = F::PLANE;
-  constexpr bool SPLIT = PassOB<R, N>::SPLIT;
+  constexpr bool SPLIT = PassOB<R, N>::SPLIT, PF = PassOB<R, N>::PF;
   constexpr long NR = long(N) * N * N;
   __shared__ cx<R> sm[PassOB<R, N>::NPL * PL];
   const PlaneWG<R, N> wg(fa);
@@ -1168,16 +1170,40 @@ __global__ void __launch_bounds__((Fz<R, N>::NTH)) k_fused_OB(const cx<R>* buf21
 #pragma unroll
     for (int c = 0; c < 3; ++c) H[i][c] = Hb[i][c] = mk<R>(R(0), R(0));
   }
+  // One round per (partner q, spin channel ch): [W0, W3] of V21 and of V12 for that channel.  With PF the
+  // next round's four planes (and, for a parallel-channel round, psi_q and chi_q at the owned points) are
+  // loaded into registers while this round is transformed; otherwise at the start of each round.
+  cx<R> pre[4][KP], pp[2][KP];
+  auto fetch = [&](int q, int ch) {
+    const long pair = long(wg.t) * fa.P + q;
+    const cx<R>* s21 = buf21 + pair * 4 * NR + wg.zo;
+    const cx<R>* s12 = buf12 + pair * 4 * NR + wg.zo;
+#pragma unroll
+    for (int i = 0; i < KP; ++i) {
+      const long o = RB * N * i;
+      pre[0][i] = s21[(2 * ch) * NR + o];
+      pre[1][i] = s21[(2 * ch + 1) * NR + o];
+      pre[2][i] = s12[(2 * ch) * NR + o];
+      pre[3][i] = s12[(2 * ch + 1) * NR + o];
+    }
+    if (ch == 0) {
+#pragma unroll
+      for (int i = 0; i < KP; ++i) {
+        pp[0][i] = psi[long(q) * NR + wg.zo + RB * N * i];
+        pp[1][i] = chi[long(q) * NR + wg.zo + RB * N * i];
+      }
+    }
+  };
+  if (PF && wg.qb < wg.qe) fetch(wg.qb, 0);
   for (int q = wg.qb; q < wg.qe; ++q) {
     const R wq = R(w[q]);
-    const long pair = long(wg.t) * fa.P + q;
     const double* del[2] = {dfr + 3 * pair_dindex(mi, ja, q, 0), dfr + 3 * pair_dindex(mi, ja, q, 1)};
-    const cx<R>* src[2] = {buf21 + pair * 4 * NR + wg.zo, buf12 + pair * 4 * NR + wg.zo};
 #pragma unroll 1
     for (int ch = 0; ch < 2; ++ch) {   // spin channel of the kernel: parallel, antiparallel
+      if (!PF) fetch(q, ch);
 #pragma unroll 1
       for (int h = 0; h < (SPLIT ? 2 : 1); ++h) {
-        // LDS rounds: unsplit, slots 0-2 V21 and 3-5 V12; split, round h holds field h in slots 0-2
+        // LDS: unsplit, slots 0-2 V21 and 3-5 V12; split, sub-round h holds field h in slots 0-2
 #pragma unroll
         for (int v = 0; v < 2; ++v) {
           if (SPLIT && v != h) continue;
@@ -1186,19 +1212,23 @@ __global__ void __launch_bounds__((Fz<R, N>::NTH)) k_fused_OB(const cx<R>* buf21
 #pragma unroll
           for (int i = 0; i < KP; ++i) {
             const int so = wg.so0 + RB * F::LD * i;
-            const long o = RB * N * i;
             const R k2 = R(double(mfreq<N>(wg.y0 + RB * i)) + del[v][1]);
-            const cx<R> w0 = src[v][(2 * ch) * NR + o];
+            const cx<R> w0 = pre[2 * v][i];
             sm[base * PL + so] = mul_i(k1 * w0);
             sm[(base + 1) * PL + so] = mul_i(k2 * w0);
-            sm[(base + 2) * PL + so] = src[v][(2 * ch + 1) * NR + o];
+            sm[(base + 2) * PL + so] = pre[2 * v + 1][i];
           }
+        }
+        if (PF && (!SPLIT || h == 1)) {   // this round's planes are in LDS: load the next round's
+          if (ch == 0)
+            fetch(q, 1);
+          else if (q + 1 < wg.qe)
+            fetch(q + 1, 0);
         }
         __syncthreads();
         planes_fft<R, N, 1>(sm, SPLIT ? 3 : 6, threadIdx.x);
 #pragma unroll
         for (int i = 0; i < KP; ++i) {
-          const long r = wg.zo + RB * N * i;
           const int so = wg.so0 + RB * F::LD * i;
           cx<R> Y[3], X12[3];
           if (!SPLIT || h == 0) {
@@ -1214,11 +1244,10 @@ __global__ void __launch_bounds__((Fz<R, N>::NTH)) k_fused_OB(const cx<R>* buf21
 #pragma unroll
             for (int c = 0; c < 3; ++c) h5[i] = h5[i] + wq * (X21[i][c] * X12[c]);
             if (ch == 0) {
-              const cx<R> pb = psi[long(q) * NR + r], xb = chi[long(q) * NR + r];
 #pragma unroll
               for (int c = 0; c < 3; ++c) {
-                H[i][c] = H[i][c] + wq * (X12[c] * pb);
-                Hb[i][c] = Hb[i][c] + wq * cmulc(X21[i][c], xb);
+                H[i][c] = H[i][c] + wq * (X12[c] * pp[0][i]);
+                Hb[i][c] = Hb[i][c] + wq * cmulc(X21[i][c], pp[1][i]);
               }
             }
           }
