@@ -161,6 +161,12 @@ int tc_apply_all_dev(tc_ctx* ctx, void* out_dev);
  * e_parts: NULL or TC_E_NPARTS doubles. */
 int tc_energy(tc_ctx* ctx, double* e_total, double* e_parts);
 
+/* Orbital energies of the last application (runs one if needed): eps receives [nk][nband]
+ * complex128, eps_j = <chi_j| T + h2 + h3 |phi_j> with the selected terms and corrections (the
+ * diagonal elements of Eqs. SCF / BITCSCF, chi = phi in TC mode; Re eps_jj is the one-electron
+ * energy of Sec. 2.3).  Per spin channel (both channels are equal). */
+int tc_orbital_energies(tc_ctx* ctx, double* eps);
+
 /* Gradient of the pseudo-energy of the loaded orbitals (the functional returned by
  * tc_energy, with the selected terms and corrections).  grad (host, may be NULL)
  * receives [nk][nband][npw_max] complex128 dE/dRe c + i dE/dIm c = 2 dE/dc* for the

@@ -62,6 +62,7 @@ def lib():
         "tc_set_jastrow": (I, [P, dp, dp]),
         "tc_set_options": (I, [P, I, D, I, ctypes.c_uint64]),
         "tc_load_orbitals": (I, [P, I, I, dp, dp, dp]),
+        "tc_orbital_energies": (I, [P, dp]),
         "tc_load_orbitals_dev": (I, [P, I, I, P, dp]),
         "tc_apply_all": (I, [P, dp]),
         "tc_apply_all_dev": (I, [P, P]),
@@ -186,6 +187,12 @@ class TCOperator:
         parts = np.zeros(len(E_PARTS))
         self._check(self._L.tc_energy(self._h, _dp(e), _dp(parts)), "tc_energy")
         return float(e[0]), dict(zip(E_PARTS, parts.tolist()))
+
+    def orbital_energies(self) -> np.ndarray:
+        """Complex eps_j = <chi_j| T + h |phi_j> per orbital of the last application, shape [nk, nband]."""
+        e = np.zeros(len(self.npw) * self.nband, dtype=np.complex128)
+        self._check(self._L.tc_orbital_energies(self._h, _dp(e.view(np.float64))), "tc_orbital_energies")
+        return e.reshape(len(self.npw), self.nband)
 
     def backward(self, want_grad=True, want_params=True):
         """(grad per k as (nband, npw) complex128 = 2 dE/dc*, dE/dA (2,), dE/dC (2,)); unrequested parts are None."""

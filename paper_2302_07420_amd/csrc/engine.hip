@@ -238,12 +238,13 @@ struct Shared {                       // precision-independent device data
   DBuf<double> out;                   // [P][npw_max] complex128 (H c)
   DBuf<double> grad;                  // [P][npw_max] complex128 energy gradient
   DBuf<double> dhc2, dhc3;            // FP64 corrections
-  DBuf<double> epart;                 // [P][4]
+  DBuf<double> epart;                 // [P][kAccSlots]
   DBuf<double> tkin;                  // [P]
   DBuf<double> S;                     // [nk][nb][nb] complex overlaps
   DBuf<double> O;                     // [nk][nb][nb] complex <c_mu | Z_j>
   DBuf<double> Zg, Wg;                // [P][npw_max] complex
   DBuf<double> ecorr;                 // [P][2]
+  DBuf<double> eps;                   // [P] complex orbital energies
 };
 
 // ------------------------------------------------------------------ FP64 helper kernels
@@ -314,6 +315,39 @@ __global__ void k_grad_finish(const double* c, const double* out, const double* 
   const double f = 4.0 * w[p];
   o[0] = f * (out[2 * id] + e * c[2 * id]);
   o[1] = f * (out[2 * id + 1] + e * c[2 * id + 1]);
+}
+
+// eps[j] = <chi_j| T + h |phi_j> = sum_G conj(cl_j) [(h c)_j + |k+G|^2/2 c_j]   (complex, one block per orbital;
+// cl = c in TC mode).  The bracket over the plane-wave set equals the one over the grid: chi_j has no
+// components outside it.
+__global__ void __launch_bounds__(256) k_orbital_eps(const double* cl, const double* c, const double* hc,
+                                                     const double* kg, const int* npw, int nb, int npw_max,
+                                                     double* eps) {
+  const int j = blockIdx.x, k = j / nb;
+  double sr = 0, si = 0;
+  for (int g = threadIdx.x; g < npw[k]; g += blockDim.x) {
+    const double* q = kg + (long(k) * npw_max + g) * 3;
+    const double e = 0.5 * (q[0] * q[0] + q[1] * q[1] + q[2] * q[2]);
+    const long o = 2 * (long(j) * npw_max + g);
+    const double yr = hc[o] + e * c[o], yi = hc[o + 1] + e * c[o + 1];
+    sr += cl[o] * yr + cl[o + 1] * yi;
+    si += cl[o] * yi - cl[o + 1] * yr;
+  }
+  __shared__ double rr[256], ri[256];
+  rr[threadIdx.x] = sr;
+  ri[threadIdx.x] = si;
+  __syncthreads();
+  for (int h = blockDim.x / 2; h > 0; h >>= 1) {
+    if (int(threadIdx.x) < h) {
+      rr[threadIdx.x] += rr[threadIdx.x + h];
+      ri[threadIdx.x] += ri[threadIdx.x + h];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    eps[2 * j] = rr[0];
+    eps[2 * j + 1] = ri[0];
+  }
 }
 
 // ------------------------------------------------------------------ biorthogonalisation (FP64)
@@ -720,7 +754,7 @@ struct EngineT : Engine {
   DBuf<cx<R>> bufB;    // [T*P][5][NR]  z-stage outputs
   DBuf<cx<R>> h4, Z;   // [T][3][NR]  h4 (Cartesian), pass-B target factor (lattice)
   DBuf<cx<R>> g;       // [T][NR]
-  DBuf<cx<double>> acc;     // [4][T][NR]  FP64 accumulation of the operator output, per energy slot
+  DBuf<cx<double>> acc;     // [kAccSlots][T][NR]  FP64 accumulation of the operator output, per energy slot
   DBuf<cx<R>> gpart;        // [S][T][3][NR]  partner-chunk partials
   DBuf<cx<R>> h4part;       // [S][T][3][NR]
   DBuf<R> h5part;           // [S][T][NR]
@@ -941,7 +975,7 @@ struct EngineT : Engine {
     h4.alloc(size_t(3) * T * NR);
     Z.alloc(size_t(3) * T * NR);
     g.alloc(size_t(T) * NR);
-    acc.alloc(size_t(4) * T * NR);
+    acc.alloc(size_t(kAccSlots) * T * NR);
     // partner chunks: enough work-groups (targets x z-planes x chunks) to fill the chip,
     // at most 64 partners per chunk (working-precision partial sums)
     S = int(std::min<long>(P, std::max<long>({1L, (2048 + long(T) * N - 1) / (long(T) * N), (P + 63L) / 64})));
@@ -1121,12 +1155,12 @@ struct EngineT : Engine {
     TC_HIP(hipEventRecord(ev.e[3], s));
 
     // ---- 3/4: target batches (pass A, pass B, local terms, r -> G)
-    const bool need_A = m.m2ax || m.m2bx1 || m.m3a3 || m.m3a4 || m.m3b4 || m.m3b6;
+    const bool need_A = m.m2ax || m.m2bx1 || m.m2bx2 || m.m3a3 || m.m3a4 || m.m3b4 || m.m3b6;
     const bool need_B = m.m2bx2 || m.m3b3 || m.m3b4 || m.m3b5;
     for (int t0 = 0; t0 < P; t0 += T) {
       const int nt = std::min(T, P - t0);
       const long npair = long(nt) * P;
-      TC_HIP(hipMemsetAsync(acc.p, 0, size_t(4) * T * NR * sizeof(cx<double>), s));
+      TC_HIP(hipMemsetAsync(acc.p, 0, size_t(kAccSlots) * T * NR * sizeof(cx<double>), s));
       TC_HIP(hipMemsetAsync(h4.p, 0, size_t(3) * T * NR * sizeof(cx<R>), s));
       for (int i = 0; i < 3; ++i) {
         hipEvent_t e;
@@ -1195,7 +1229,7 @@ struct EngineT : Engine {
       K(TC_K_OTHER, fb * 16.0 * nt + 8.0 * fd * nt, [&] {
         hipLaunchKernelGGL((k_local<R, N>), dim3(nblk(long(nt) * NR)), dim3(256), 0, s, psi.p, D.p, loc.p, h4.p, t0,
                            nt, P, m, acc.p, g.p);
-        hipLaunchKernelGGL((k_epart<R, N>), dim3(4 * nt), dim3(256), 0, s, X, acc.p, t0, nt, sh.epart.p);
+        hipLaunchKernelGGL((k_epart<R, N>), dim3(kAccSlots * nt), dim3(256), 0, s, X, acc.p, t0, nt, sh.epart.p);
       });
       fft3d_t<R, N>(g.p, nt, -1, s, pf);
       K(TC_K_OTHER, 0.0, [&] {
@@ -1366,6 +1400,7 @@ struct tc_ctx {
   bool have_result = false;
   std::vector<double> hcoef;   // [P][npw_max] complex staging
   double e_total = 0, e_parts[TC_E_NPARTS] = {0, 0, 0, 0};
+  std::vector<double> eps;   // [P] complex orbital energies of the last application
   double stage_ms[6] = {0, 0, 0, 0, 0, 0};
   double total_ms = 0;
   Prof prof;
@@ -1432,18 +1467,22 @@ int prepare(tc_ctx* c) {
 void finish_energy(tc_ctx* c) {
   Problem& pb = c->pb;
   const int P = pb.P();
-  std::vector<double> ep(size_t(4) * P), tk(P), ec(size_t(2) * P);
+  const Masks m = make_masks(pb.mask);
+  std::vector<double> ep(size_t(kAccSlots) * P), tk(P), ec(size_t(2) * P);
   TC_HIP(hipMemcpy(ep.data(), c->sh.epart.p, ep.size() * sizeof(double), hipMemcpyDeviceToHost));
   TC_HIP(hipMemcpy(tk.data(), c->sh.tkin.p, tk.size() * sizeof(double), hipMemcpyDeviceToHost));
   TC_HIP(hipMemcpy(ec.data(), c->sh.ecorr.p, ec.size() * sizeof(double), hipMemcpyDeviceToHost));
   double T = 0, E2 = 0, E3 = 0, EC = 0;
   for (int p = 0; p < P; ++p) {
     const double f = pb.occ[p] * 2.0 / pb.nk;   // both spin channels
+    const double* e = &ep[size_t(kAccSlots) * p];
     T += f * tk[p];
-    // <2bh2>+<2bx2> equals <2bh1>+<2bx1> (transposition of the discrete kernels), so the
-    // two-body part is (1/2)<2ah+2ax> + <2bh1+2bx1> and pass B's 2bx2 leaves the three-body part.
-    E2 += f * (0.5 * ep[4 * p] + ep[4 * p + 1]);
-    E3 += f * (ep[4 * p + 2] + ep[4 * p + 3] - ep[4 * p + 1]) / 3.0;
+    // Two-body terms count 1/2, three-body terms 1/3 (multiplicities are in the operator).  Pass B (slot 3)
+    // fuses 2bx2 with 3b3-3b5; the 2bx2 bracket equals the 2bx1 bracket (slot 1, accumulated whenever
+    // either is selected) because the discrete kernels are transposes of each other, so it is moved from
+    // the 1/3 to the 1/2 group through slot 1.
+    E2 += f * 0.5 * (e[0] + e[4] + e[5] + (m.m2bx1 + m.m2bx2) * e[1]);
+    E3 += f * (e[2] + e[3] - m.m2bx2 * e[1]) / 3.0;
     E2 += f * 0.5 * ec[2 * p];
     E3 += f * ec[2 * p + 1] / 3.0;
     EC += f * (0.5 * ec[2 * p] + ec[2 * p + 1] / 3.0);
@@ -1465,15 +1504,20 @@ void run_apply(tc_ctx* c, void* out_dev, double* out_host) {
   sh.dhc3.alloc(size_t(2) * P * pb.npw_max);
   sh.Zg.alloc(size_t(2) * P * pb.npw_max);
   sh.Wg.alloc(size_t(2) * P * pb.npw_max);
-  sh.epart.alloc(size_t(4) * P);
+  sh.epart.alloc(size_t(kAccSlots) * P);
   sh.tkin.alloc(P);
   sh.ecorr.alloc(size_t(2) * P);
   sh.S.alloc(size_t(2) * pb.nk * pb.nb * pb.nb);
   sh.O.alloc(size_t(2) * pb.nk * pb.nb * pb.nb);
+  sh.eps.alloc(size_t(2) * P);
   c->eng->prof = &c->prof;
   c->eng->apply(c->stream, sh, pb, c->stage_ms);
   c->total_ms = 0;
   for (double v : c->stage_ms) c->total_ms += v;
+  hipLaunchKernelGGL(k_orbital_eps, dim3(P), dim3(256), 0, c->stream, pb.bitc ? sh.coefL.p : sh.coef.p, sh.coef.p,
+                     sh.out.p, sh.kg.p, sh.npw.p, pb.nb, pb.npw_max, sh.eps.p);
+  c->eps.resize(size_t(2) * P);
+  TC_HIP(hipMemcpyAsync(c->eps.data(), sh.eps.p, c->eps.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
   if (out_dev)
     TC_HIP(hipMemcpyAsync(out_dev, sh.out.p, size_t(2) * P * pb.npw_max * sizeof(double), hipMemcpyDeviceToDevice,
                           c->stream));
@@ -1521,6 +1565,7 @@ int do_backward(tc_ctx* c, void* grad_dev, double* grad_host, double* dA, double
     uint64_t mask;
     double e, parts[TC_E_NPARTS], stage[6], total;
     bool had;
+    std::vector<double> eps;
     ~Keep() {
       c->pb.mask = mask;
       c->tables_dirty = true;   // the next application rebuilds the operator's tables
@@ -1529,8 +1574,9 @@ int do_backward(tc_ctx* c, void* grad_dev, double* grad_host, double* dA, double
       std::memcpy(c->stage_ms, stage, sizeof(stage));
       c->total_ms = total;
       c->have_result = had;
+      c->eps = eps;
     }
-  } keep{c, m, c->e_total, {}, {}, c->total_ms, c->have_result};
+  } keep{c, m, c->e_total, {}, {}, c->total_ms, c->have_result, c->eps};
   std::memcpy(keep.parts, c->e_parts, sizeof(keep.parts));
   std::memcpy(keep.stage, c->stage_ms, sizeof(keep.stage));
   Shared& sh = c->sh;
@@ -1858,11 +1904,20 @@ int tc_apply_all_dev(tc_ctx* c, void* out_dev) {
   return guard(c, [&]() -> int { return do_apply(c, out_dev, nullptr); });
 }
 
+int tc_orbital_energies(tc_ctx* c, double* eps) {
+  return guard(c, [&]() -> int {
+    if (!eps) return fail(c, TC_ERR_ARG, "null output");
+    if (!c->have_result) {
+      int st = do_apply(c, nullptr, nullptr);
+      if (st != TC_OK) return st;
+    }
+    std::memcpy(eps, c->eps.data(), c->eps.size() * sizeof(double));
+    return TC_OK;
+  });
+}
+
 int tc_energy(tc_ctx* c, double* e_total, double* e_parts) {
   return guard(c, [&]() -> int {
-    const uint64_t m = c->pb.mask;
-    if (((m & TC_T_2BH1) != 0) != ((m & TC_T_2BH2) != 0) || ((m & TC_T_2BX1) != 0) != ((m & TC_T_2BX2) != 0))
-      return fail(c, TC_ERR_UNSUPPORTED, "energy needs 2bh1/2bh2 and 2bx1/2bx2 selected together");
     if (!c->have_result) {
       int st = do_apply(c, nullptr, nullptr);
       if (st != TC_OK) return st;

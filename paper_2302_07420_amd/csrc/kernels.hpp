@@ -875,7 +875,9 @@ __global__ void __launch_bounds__((Fz<R, N>::NTH)) k_fused_A(const cx<R>* buf5, 
     for (int s = 0; s < 3; ++s) ga[i][s] = h4[i][s] = mk<R>(R(0), R(0));
     nk[i] = ldo(n, ob[i]);
   }
-  const R a0 = R(-m.m2ax), a1 = R(-m.m2bx1), a2 = R(-m.m3a4);
+  // 2bx1 is accumulated (into its own slot) whenever 2bx1 or 2bx2 is selected: its bracket is also the
+  // energy of 2bx2, which pass B fuses with three-body terms
+  const R a0 = R(-m.m2ax), a1 = R((m.m2bx1 != 0 || m.m2bx2 != 0) ? -1 : 0), a2 = R(-m.m3a4);
   // the next partner's five pair planes are loaded into registers while this partner is transformed
   cx<R> pre[5][KP];
   auto fetch = [&](int q) {
@@ -1361,9 +1363,12 @@ __global__ void k_sum_parts(int mode, int S, int T, int t0, int slot, const R* h
   }
 }
 
-// Local (Hartree-type) terms added to the FP64 accumulators, then g_t = sum of the four slots.
-// loc: [VH, h1 x3, P2bh2, F3b1, h6, F3b2]; D is stored component-major D[(c*P + p)*N^3 + r].
-// acc slots: 0 = 2ah/2ax, 1 = 2bh1/2bx1, 2 = other three-body terms, 3 = pass B + 2bh2.
+// Local (Hartree-type) terms added to the FP64 accumulators, then g_t = sum of the slots that belong to
+// the operator.  loc: [VH, h1 x3, P2bh2, F3b1, h6, F3b2]; D is stored component-major D[(c*P + p)*N^3 + r].
+// acc slots (kAccSlots): 0 = 2ah + 2ax, 1 = 2bx1 (kept out of g unless 2bx1 is selected), 2 = three-body
+// terms outside pass B, 3 = pass B (2bx2, 3b3, 3b4, 3b5), 4 = 2bh1, 5 = 2bh2.
+constexpr int kAccSlots = 6;
+
 template <typename R, int N>
 __global__ void k_local(const cx<R>* psi, const cx<R>* D, const cx<R>* loc, const cx<R>* h4, int t0, int T, int P,
                         Masks m, cx<double>* acc, cx<R>* g) {
@@ -1388,25 +1393,29 @@ __global__ void k_local(const cx<R>* psi, const cx<R>* D, const cx<R>* loc, cons
     h14 = h14 + h1[c] * h4[(long(t) * 3 + c) * NR + r];
   }
   const cx<R> s3 = R(-0.5 * m.m3a1) * hh - R(m.m3b1) * F3b1 + R(0.5 * m.m3a2) * h6 + R(m.m3b2) * F3b2;
-  const cx<R> v[4] = {(R(m.m2ah) * VH) * pj, R(m.m2bh1) * hD, s3 * pj + R(m.m3a3) * h14, (R(m.m2bh2) * P2) * pj};
+  const cx<R> v[kAccSlots] = {(R(m.m2ah) * VH) * pj, mk<R>(R(0), R(0)), s3 * pj + R(m.m3a3) * h14,
+                              mk<R>(R(0), R(0)), R(m.m2bh1) * hD, (R(m.m2bh2) * P2) * pj};
   double gx = 0, gy = 0;
 #pragma unroll
-  for (int s = 0; s < 4; ++s) {
+  for (int s = 0; s < kAccSlots; ++s) {
     cx<double>& a = acc[s * TS + long(t) * NR + r];
     a.x += double(v[s].x);
     a.y += double(v[s].y);
-    gx += a.x;
-    gy += a.y;
+    if (s != 1 || m.m2bx1 != 0) {
+      gx += a.x;
+      gy += a.y;
+    }
   }
   g[long(t) * NR + r] = mk<R>(R(gx), R(gy));
 }
 
-// Energy partials: e[j*4 + slot] = Re sum_r conj(psi_j) acc_slot,t / N^3 (deterministic tree, one block per (t, slot))
+// Energy partials: e[j*kAccSlots + slot] = Re sum_r conj(chi_j) acc_slot,t / N^3 (deterministic tree, one block
+// per (t, slot); chi = psi in TC mode)
 template <typename R, int N>
-__global__ void __launch_bounds__(256) k_epart(const cx<R>* psi, const cx<double>* acc, int t0, int T, double* e) {
+__global__ void __launch_bounds__(256) k_epart(const cx<R>* chi, const cx<double>* acc, int t0, int T, double* e) {
   constexpr long NR = long(N) * N * N;
-  const int t = blockIdx.x / 4, slot = blockIdx.x % 4;
-  const cx<R>* p = psi + long(t0 + t) * NR;
+  const int t = blockIdx.x / kAccSlots, slot = blockIdx.x % kAccSlots;
+  const cx<R>* p = chi + long(t0 + t) * NR;
   const cx<double>* a = acc + (long(slot) * T + t) * NR;
   double s = 0;
   for (long r = threadIdx.x; r < NR; r += blockDim.x) s += double(p[r].x) * a[r].x + double(p[r].y) * a[r].y;
@@ -1417,7 +1426,7 @@ __global__ void __launch_bounds__(256) k_epart(const cx<R>* psi, const cx<double
     if (int(threadIdx.x) < h) red[threadIdx.x] += red[threadIdx.x + h];
     __syncthreads();
   }
-  if (threadIdx.x == 0) e[long(t0 + t) * 4 + slot] = red[0] / double(NR);
+  if (threadIdx.x == 0) e[long(t0 + t) * kAccSlots + slot] = red[0] / double(NR);
 }
 
 // h6 = sum_a w_a h5[a];  M_c = sum_a w_a conj(H3c[a]_c) psi_a, H3c = conj(H3b) (Alg. 3b2 source;

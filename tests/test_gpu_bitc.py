@@ -189,3 +189,25 @@ def test_bench_shape_sampled_targets_fp64(bench_bitc):
     err = relerr(got, exp_rows)
     _say(f"    max element error / max |h c| = {err:.3e}")
     assert err < FP64_TOL
+
+
+def test_orbital_energies_and_single_term_energies_fp64(case):
+    name, w, per, tot, E = case
+    pr = Problem(w)
+    g = {t: pr.term(t, 0) for t in ALL_TERMS}
+    kin = pr.kinetic().numpy()
+    f = pr.orb[0]["f"].numpy()
+    T0 = 2 * np.sum(f * kin).real / pr.nk
+    eps = kin + pr.braket(0, sum(MULT.get(t, 1) * g[t] for t in ALL_TERMS)).numpy()
+    _say(f"[gpu] bitc {name} fp64 orbital energies and single-term energies")
+    op = tc.from_workload(w, precision=tc.TC_PREC_FP64)
+    got = op.orbital_energies().reshape(-1)
+    op.close()
+    assert np.abs(got - eps).max() < FP64_TOL * np.abs(eps).max()
+    for t in ("2bh2", "2bx2", "3b5", "3a2"):
+        fac = 0.5 if t.startswith("2") else MULT.get(t, 1) / 3.0
+        Et = T0 + 2 * fac * float(np.sum(f * pr.braket(0, g[t]).numpy()).real) / pr.nk
+        op = tc.from_workload(w, precision=tc.TC_PREC_FP64, terms=tc.TERM_BITS[t] | tc.TERM_BITS["corr"])
+        Eg, _ = op.energy()
+        op.close()
+        assert abs(Eg - Et) < FP64_TOL * abs(Et), (t, Eg, Et)

@@ -63,6 +63,14 @@ def test_electron_gas_54_every_element(prec, tol):
     assert err < tol
     Eh, _ = heg_energy(w)
     assert abs(Eg - Eh) < (FP64_TOL if prec == "fp64" else 1e-6) * abs(Eh)
+    # orbital energies: |k+G|^2/2 + the eigenvalue of h2 + h3 (Sec. 2.3: Re eps is the band energy)
+    op = tc.from_workload(w, precision=tc.TC_PREC_FP64 if prec == "fp64" else tc.TC_PREC_FP32)
+    eps = op.orbital_energies().reshape(-1)
+    op.close()
+    exp_eps = 0.5 * np.sum(p * p, 1) + lam
+    eerr = np.abs(eps - exp_eps).max() / np.abs(exp_eps).max()
+    _say(f"    orbital energies: max error / max |eps| = {eerr:.3e}")
+    assert eerr < tol
 
 
 def _sampled(w, targets, terms, prec, tol, batch=0):

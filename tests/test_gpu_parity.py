@@ -25,6 +25,21 @@ def oracle(w, terms=ALL_TERMS, div=True):
     return per, tot, float(pr.energy(terms=terms))
 
 
+def oracle_energies(w):
+    """Energy with each term alone (kinetic included) and the orbital energies <chi|T + h|phi>."""
+    pr = Problem(w)
+    g = {t: pr.term(t, 0) for t in ALL_TERMS}
+    kin = pr.kinetic().numpy()
+    f = pr.orb[0]["f"].numpy()
+    T = 2 * np.sum(f * kin).real / pr.nk
+    E1 = {}
+    for t in ALL_TERMS:
+        fac = 0.5 if t.startswith("2") else MULT.get(t, 1) / 3.0
+        E1[t] = T + 2 * fac * float(np.sum(f * pr.braket(0, g[t]).numpy()).real) / pr.nk
+    eps = kin + pr.braket(0, sum(MULT.get(t, 1) * g[t] for t in ALL_TERMS)).numpy()
+    return E1, eps
+
+
 def relerr(a, b):
     scale = max(np.abs(x).max() for x in b)
     return max(np.abs(x - y).max() for x, y in zip(a, b)) / scale
@@ -127,3 +142,30 @@ def test_error_paths():
     with pytest.raises(tc.TCError, match="status -1"):
         op.set_jastrow([1.0, 1.0], [0.0, 1.0])
     op.close()
+
+
+def test_energy_of_every_single_term_fp64(case):
+    """Every term alone (with its correction), including 2bh2 and 2bx2 without their partners."""
+    name, w, _ = case
+    E1, _ = oracle_energies(w)
+    for t in ALL_TERMS:
+        _say(f"[gpu] {name} fp64 energy of term {t} alone")
+        op = tc.from_workload(w, precision=tc.TC_PREC_FP64, terms=tc.TERM_BITS[t] | tc.TERM_BITS["corr"])
+        Eg, _ = op.energy()
+        op.close()
+        assert abs(Eg - E1[t]) < FP64_TOL * abs(E1[t]), (t, Eg, E1[t])
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", FP64_TOL), ("fp32", FP32_TOL)])
+def test_orbital_energies(case, prec, tol):
+    name, w, _ = case
+    _, eps = oracle_energies(w)
+    _say(f"[gpu] {name} {prec} orbital energies")
+    op = tc.from_workload(w, precision=tc.TC_PREC_FP64 if prec == "fp64" else tc.TC_PREC_FP32)
+    got = op.orbital_energies().reshape(-1)
+    g2 = op.orbital_energies().reshape(-1)
+    op.close()
+    err = np.abs(got - eps).max() / np.abs(eps).max()
+    _say(f"    max |eps - eps_oracle| / max |eps| = {err:.3e}")
+    assert err < tol
+    np.testing.assert_array_equal(got, g2)
