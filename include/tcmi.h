@@ -161,6 +161,19 @@ int tc_apply_all_dev(tc_ctx* ctx, void* out_dev);
  * e_parts: NULL or TC_E_NPARTS doubles. */
 int tc_energy(tc_ctx* ctx, double* e_total, double* e_parts);
 
+/* Apply the operator that the loaded orbitals define (h2 + h3 with the selected terms and
+ * corrections, Eqs. SCF / BITCSCF, without the kinetic term) to nvec trial vectors per k-point, as
+ * the block-Davidson iteration of Sec. 2.4 needs.  in and out are [nk][nvec][npw_max] complex128,
+ * vector v of k-point k at (k*nvec + v); input beyond npw(k) is ignored, output beyond it is zero.
+ * Every term is linear in the target: the occupied set supplies the densities, partner sums and
+ * corrections, and the trial vectors take the target role (phi_j in the algorithms).  The results of
+ * the last tc_apply_all* (energies, orbital energies) are not changed.  TC_ERR_ARG for nvec <= 0 or
+ * null buffers. */
+int tc_apply(tc_ctx* ctx, int nvec, const double* in, double* out);
+
+/* Same, with caller-owned device buffers of the same layout.  Synchronous. */
+int tc_apply_dev(tc_ctx* ctx, int nvec, const void* in_dev, void* out_dev);
+
 /* Orbital energies of the last application (runs one if needed): eps receives [nk][nband]
  * complex128, eps_j = <chi_j| T + h2 + h3 |phi_j> with the selected terms and corrections (the
  * diagonal elements of Eqs. SCF / BITCSCF, chi = phi in TC mode; Re eps_jj is the one-electron

@@ -63,6 +63,8 @@ def lib():
         "tc_set_options": (I, [P, I, D, I, ctypes.c_uint64]),
         "tc_load_orbitals": (I, [P, I, I, dp, dp, dp]),
         "tc_orbital_energies": (I, [P, dp]),
+        "tc_apply": (I, [P, I, dp, dp]),
+        "tc_apply_dev": (I, [P, I, P, P]),
         "tc_load_orbitals_dev": (I, [P, I, I, P, dp]),
         "tc_apply_all": (I, [P, dp]),
         "tc_apply_all_dev": (I, [P, P]),
@@ -187,6 +189,26 @@ class TCOperator:
         parts = np.zeros(len(E_PARTS))
         self._check(self._L.tc_energy(self._h, _dp(e), _dp(parts)), "tc_energy")
         return float(e[0]), dict(zip(E_PARTS, parts.tolist()))
+
+    def apply_vectors(self, vecs) -> List[np.ndarray]:
+        """h v for trial vectors: ``vecs`` per k-point (nvec, npw(k)), the same nvec everywhere."""
+        nk = len(self.npw)
+        nvec = np.asarray(vecs[0]).shape[0]
+        buf = np.zeros((nk, nvec, self.npw_max), dtype=np.complex128)
+        for k in range(nk):
+            v = np.asarray(vecs[k], dtype=np.complex128)
+            if v.shape != (nvec, self.npw[k]):
+                raise ValueError(f"k-point {k}: vectors of shape {v.shape}, expected {(nvec, self.npw[k])}")
+            buf[k, :, : self.npw[k]] = v
+        out = np.zeros_like(buf)
+        self._check(self._L.tc_apply(self._h, nvec, _dp(buf.view(np.float64)), _dp(out.view(np.float64))),
+                    "tc_apply")
+        return [out[k, :, : self.npw[k]].copy() for k in range(nk)]
+
+    def apply_vectors_dev(self, nvec: int, in_ptr: int, out_ptr: int):
+        """Device form of apply_vectors: [nk][nvec][npw_max] complex128 buffers (synchronous)."""
+        self._check(self._L.tc_apply_dev(self._h, int(nvec), ctypes.c_void_p(in_ptr), ctypes.c_void_p(out_ptr)),
+                    "tc_apply_dev")
 
     def orbital_energies(self) -> np.ndarray:
         """Complex eps_j = <chi_j| T + h |phi_j> per orbital of the last application, shape [nk, nband]."""

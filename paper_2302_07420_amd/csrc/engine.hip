@@ -245,15 +245,18 @@ struct Shared {                       // precision-independent device data
   DBuf<double> Zg, Wg;                // [P][npw_max] complex
   DBuf<double> ecorr;                 // [P][2]
   DBuf<double> eps;                   // [P] complex orbital energies
+  // target-set side of the corrections (tc_apply)
+  DBuf<double> ZgT, WgT, dhc2T, dhc3T, ST, OT, ecorrT;
 };
 
 // ------------------------------------------------------------------ FP64 helper kernels
-__global__ void k_overlap(const double* a, const double* b, const int* npw, int nb, int npw_max, int nk, double* S) {
-  // S[k][m][n] = sum_g conj(a_km[g]) b_kn[g]
+__global__ void k_overlap(const double* a, int na, const double* b, int nbb, const int* npw, int npw_max, int nk,
+                          double* S) {
+  // S[k][m][n] = sum_g conj(a_km[g]) b_kn[g], m < na (rows of a per k), n < nbb (rows of b per k)
   const int id = blockIdx.x;
-  const int k = id / (nb * nb), m = (id / nb) % nb, n = id % nb;
-  const double* x = a + 2 * (long(k * nb + m) * npw_max);
-  const double* y = b + 2 * (long(k * nb + n) * npw_max);
+  const int k = id / (na * nbb), m = (id / nbb) % na, n = id % nbb;
+  const double* x = a + 2 * (long(k * na + m) * npw_max);
+  const double* y = b + 2 * (long(k * nbb + n) * npw_max);
   double sr = 0, si = 0;
   for (int g = threadIdx.x; g < npw[k]; g += blockDim.x) {
     sr += x[2 * g] * y[2 * g] + x[2 * g + 1] * y[2 * g + 1];
@@ -522,22 +525,24 @@ __global__ void k_corr_products(const cx<double>* F, const cx<double>* psi, int 
 //  dhc3_j = 1/2 const1 c_j + 1/2 W_j                                          (3a2, Eqs. divcor_3a2_*)
 //         + 2 sum_mu f_mu { [c1s n0 S(mu,j)/Omega + O(mu,j)/Omega] c_mu + (S(mu,j)/Omega) Z_mu }  (3b6 x 2)
 // const1 and c1s n0 are complex (imaginary parts zero in TC mode).
-__global__ void k_corr_apply(const double* c, const double* S, const double* O, const double* Z, const double* W,
-                             const double* f, const int* npw, int nb, int npw_max, int P, double omega, double m2ax,
-                             double dgb, double m3a2, double const1, double const1i, double m3b6, double c1s_n0,
-                             double c1s_n0i, double* dhc2, double* dhc3) {
+// Targets j (coefficients cT, nbt per k-point) may differ from the occupied set c (nb per k-point);
+// S and O are then [k][mu][jb] with rows of length nbt, and W is per target.
+__global__ void k_corr_apply(const double* cT, const double* c, const double* S, const double* O, const double* Z,
+                             const double* W, const double* f, const int* npw, int nb, int nbt, int npw_max, int NT,
+                             double omega, double m2ax, double dgb, double m3a2, double const1, double const1i,
+                             double m3b6, double c1s_n0, double c1s_n0i, double* dhc2, double* dhc3) {
   const long id = long(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (id >= long(P) * npw_max) return;
+  if (id >= long(NT) * npw_max) return;
   const int j = int(id / npw_max), g = int(id - long(j) * npw_max);
-  const int k = j / nb, jb = j % nb;
+  const int k = j / nbt, jb = j % nbt;
   double a2r = 0, a2i = 0, a3r = 0, a3i = 0;
   if (g < npw[k]) {
-    const double* cj = c + 2 * (long(j) * npw_max + g);
+    const double* cj = cT + 2 * (long(j) * npw_max + g);
     for (int mu = 0; mu < nb; ++mu) {
       const int q = k * nb + mu;
       const double* cq = c + 2 * (long(q) * npw_max + g);
       const double* zq = Z + 2 * (long(q) * npw_max + g);
-      const long si = 2 * ((long(k) * nb + mu) * nb + jb);
+      const long si = 2 * ((long(k) * nb + mu) * nbt + jb);
       const double sr = S[si] / omega, sim = S[si + 1] / omega;
       const double orr = O[si] / omega, oi = O[si + 1] / omega;
       // 2ax
@@ -699,10 +704,19 @@ void fft3d_t(cx<R>* d, long nvol, int dir, hipStream_t s, Prof* pf = nullptr) {
 }
 
 // ------------------------------------------------------------------ engine
+// Trial vectors of tc_apply: nvec per k-point, device coefficients [nk][nvec][npw_max] (complex128), and the
+// output of the same layout.  Without a target set the targets are the loaded orbitals themselves.
+struct TargetSet {
+  const double* coef = nullptr;
+  int nvec = 0;
+  double* out = nullptr;
+};
+
 struct Engine {
   virtual ~Engine() = default;
   virtual void upload_tables(const Problem& pb, const TableVariant& tv) = 0;
-  virtual void apply(hipStream_t s, Shared& sh, const Problem& pb, double* stage_ms) = 0;
+  virtual void apply(hipStream_t s, Shared& sh, const Problem& pb, double* stage_ms,
+                     const TargetSet* ts = nullptr) = 0;
   Prof* prof = nullptr;
 };
 
@@ -767,6 +781,9 @@ struct EngineT : Engine {
   DBuf<cx<R>> Hbpart;       // [S][T][3][NR]
   DBuf<cx<double>> chi64;   // [P][NR]  FP64 left orbitals for the corrections
   bool bitc_alloc = false;
+  // target set of tc_apply (trial vectors)
+  DBuf<cx<R>> psiT, DT;              // [NT][NR], [3][NT][NR]
+  DBuf<cx<double>> psiT64, prodT;    // [NT][NR], [2][NT][NR]
   int S = 1;
   // kernel tables (scaled by 1/(Omega N^3))
   DBuf<R> tV, tU1, tU2, tHV, tHU;
@@ -1000,12 +1017,16 @@ struct EngineT : Engine {
     bitc_alloc = pb.bitc;
   }
 
-  void apply(hipStream_t s, Shared& sh, const Problem& pb, double* stage_ms) override {
+  void apply(hipStream_t s, Shared& sh, const Problem& pb, double* stage_ms, const TargetSet* ts) override {
     const int P = pb.P();
     const int nb = pb.nb;
     const Masks m = make_masks(pb.mask);
     ensure(pb, size_t(8) << 30);
-    const MeshInfo mi{pb.n1, pb.n2, pb.n3, nb, P};
+    // targets: the orbitals, or nbt trial vectors per k-point
+    const int nbt = ts ? ts->nvec : nb;
+    const int NTG = pb.nk * nbt;
+    const MeshInfo mi{pb.n1, pb.n2, pb.n3, nb, P, nb};     // occupied-occupied pass
+    const MeshInfo miT{pb.n1, pb.n2, pb.n3, nb, P, nbt};   // target passes
     Recip rc;
     for (int i = 0; i < 9; ++i) rc.b[i] = pb.B[i];
     Basis<R> bm, mm;   // B_dc = (b_d)_c and the metric M = B B^T, working precision
@@ -1047,6 +1068,24 @@ struct EngineT : Engine {
     });
     fft3d_t<R, N>(psi.p, P, +1, s, pf);
     if (bitc) fft3d_t<R, N>(chi.p, P, +1, s, pf);
+    if (ts) {
+      psiT.alloc(size_t(NTG) * NR);
+      DT.alloc(size_t(3) * NTG * NR);
+      TC_HIP(hipMemsetAsync(psiT.p, 0, size_t(NTG) * NR * sizeof(cx<R>), s));
+      TC_HIP(hipMemsetAsync(DT.p, 0, size_t(3) * NTG * NR * sizeof(cx<R>), s));
+      const unsigned gst = nblk(long(NTG) * pb.npw_max);
+      K(TC_K_SCATTER, 0.0, [&] {
+        hipLaunchKernelGGL((k_scatter<R>), dim3(gst), dim3(256), 0, s, ts->coef, sh.boxidx.p, sh.npw.p, sh.kg.p, nbt,
+                           pb.npw_max, NTG, -1, psiT.p, NR);
+        for (int c = 0; c < 3; ++c)
+          hipLaunchKernelGGL((k_scatter<R>), dim3(gst), dim3(256), 0, s, ts->coef, sh.boxidx.p, sh.npw.p, sh.kg.p,
+                             nbt, pb.npw_max, NTG, c, DT.p + size_t(c) * NTG * NR, NR);
+      });
+      fft3d_t<R, N>(psiT.p, NTG, +1, s, pf);
+      fft3d_t<R, N>(DT.p, 3L * NTG, +1, s, pf);
+    }
+    const cx<R>* tP = ts ? psiT.p : psi.p;   // target fields
+    const cx<R>* tD = ts ? DT.p : D.p;
     fft3d_t<R, N>(D.p, 3L * P, +1, s, pf);
     K(TC_K_OTHER, 6.0 * fb * P, [&] {
       hipLaunchKernelGGL((k_lattice3<R, N>), dim3(nblk(long(P) * NR)), dim3(256), 0, s, D.p, Dl.p, bm, long(P), NR,
@@ -1157,8 +1196,8 @@ struct EngineT : Engine {
     // ---- 3/4: target batches (pass A, pass B, local terms, r -> G)
     const bool need_A = m.m2ax || m.m2bx1 || m.m2bx2 || m.m3a3 || m.m3a4 || m.m3b4 || m.m3b6;
     const bool need_B = m.m2bx2 || m.m3b3 || m.m3b4 || m.m3b5;
-    for (int t0 = 0; t0 < P; t0 += T) {
-      const int nt = std::min(T, P - t0);
+    for (int t0 = 0; t0 < NTG; t0 += T) {
+      const int nt = std::min(T, NTG - t0);
       const long npair = long(nt) * P;
       TC_HIP(hipMemsetAsync(acc.p, 0, size_t(kAccSlots) * T * NR * sizeof(cx<double>), s));
       TC_HIP(hipMemsetAsync(h4.p, 0, size_t(3) * T * NR * sizeof(cx<R>), s));
@@ -1173,15 +1212,15 @@ struct EngineT : Engine {
       if (need_A) {
         const FusedArgs fa{P, nt, t0, S, chunk};
         K(TC_K_XY_PAIR_TGT, fb * (npair + nt + P), [&] {
-          hipLaunchKernelGGL((k_pair_xy<R, N, false>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, X, psi.p, fa,
+          hipLaunchKernelGGL((k_pair_xy<R, N, false>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, X, tP, fa,
                              bufA.p);
         });
         K(TC_K_ZCONV_A1, fb * 6.0 * npair + tabB, [&] {
-          zconv<OP_A1>(s, npair, t0, mi, tb, 1);
+          zconv<OP_A1>(s, npair, t0, miT, tb, 1);
         });
         K(TC_K_FUSED_A, fb * ((m.m3b6 ? 9.0 : 5.0) * npair + 8.0 * P + nt) + 6.0 * part, [&] {
           hipLaunchKernelGGL((k_fused_A<R, N>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, bufB.p, psi.p, Dl.p,
-                             Hl.p, nJ.p, sh.w.p, fa, m, int(m.m3b6 != 0), mi, bm, mm, dfr.p, bufA.p, gpart.p,
+                             Hl.p, nJ.p, sh.w.p, fa, m, int(m.m3b6 != 0), miT, bm, mm, dfr.p, bufA.p, gpart.p,
                              h4part.p);
         });
         K(TC_K_SUM_PARTS, 6.0 * part + 6.0 * fd * nt + 3.0 * fb * nt, [&] {
@@ -1190,7 +1229,7 @@ struct EngineT : Engine {
         });
         if (m.m3b6) {
           K(TC_K_ZCONV_A2, fb * 5.0 * npair + tabB, [&] {
-            zconv<OP_A2>(s, npair, t0, mi, tb, 1);
+            zconv<OP_A2>(s, npair, t0, miT, tb, 1);
           });
           K(TC_K_FUSED_Y, fb * (npair + P) + part, [&] {
             hipLaunchKernelGGL((k_fused_Y<R, N>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, bufB.p, psi.p,
@@ -1206,15 +1245,15 @@ struct EngineT : Engine {
       if (need_B) {
         const FusedArgs fy{P, nt, t0, S, chunk};
         K(TC_K_OTHER, fb * 13.0 * nt, [&] {
-          hipLaunchKernelGGL((k_passB_Z<R, N>), dim3(nblk(long(nt) * NR)), dim3(256), 0, s, psi.p, D.p, loc.p + NR,
-                             h4.p, t0, nt, P, m, bm, Z.p);
+          hipLaunchKernelGGL((k_passB_Z<R, N>), dim3(nblk(long(nt) * NR)), dim3(256), 0, s, tP, tD, loc.p + NR,
+                             h4.p, t0, nt, NTG, m, bm, Z.p);
         });
         K(TC_K_XY_PASSB, fb * (2.0 * npair + 4.0 * P + 4.0 * nt), [&] {
-          hipLaunchKernelGGL((k_passB_xy<R, N>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, psi.p, X, Z.p,
-                             bitc ? H3bc.p : Hl.p, fy, mi, dfr.p, R(m.m3b5), bufA.p);
+          hipLaunchKernelGGL((k_passB_xy<R, N>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, tP, X, Z.p,
+                             bitc ? H3bc.p : Hl.p, fy, miT, dfr.p, R(m.m3b5), bufA.p);
         });
         K(TC_K_ZCONV_B, fb * 3.0 * npair + tabB, [&] {
-          zconv<OP_B>(s, npair, t0, mi, tb, 1);
+          zconv<OP_B>(s, npair, t0, miT, tb, 1);
         });
         K(TC_K_FUSED_Y, fb * (npair + P) + part, [&] {
           hipLaunchKernelGGL((k_fused_Y<R, N>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, bufB.p, psi.p, sh.w.p,
@@ -1227,24 +1266,27 @@ struct EngineT : Engine {
       }
       TC_HIP(hipEventRecord(be[2], s));
       K(TC_K_OTHER, fb * 16.0 * nt + 8.0 * fd * nt, [&] {
-        hipLaunchKernelGGL((k_local<R, N>), dim3(nblk(long(nt) * NR)), dim3(256), 0, s, psi.p, D.p, loc.p, h4.p, t0,
-                           nt, P, m, acc.p, g.p);
-        hipLaunchKernelGGL((k_epart<R, N>), dim3(kAccSlots * nt), dim3(256), 0, s, X, acc.p, t0, nt, sh.epart.p);
+        hipLaunchKernelGGL((k_local<R, N>), dim3(nblk(long(nt) * NR)), dim3(256), 0, s, tP, tD, loc.p, h4.p, t0,
+                           nt, NTG, m, acc.p, g.p);
+        if (!ts)
+          hipLaunchKernelGGL((k_epart<R, N>), dim3(kAccSlots * nt), dim3(256), 0, s, X, acc.p, t0, nt, sh.epart.p);
       });
       fft3d_t<R, N>(g.p, nt, -1, s, pf);
       K(TC_K_OTHER, 0.0, [&] {
         hipLaunchKernelGGL((k_gather<R>), dim3(nblk(long(nt) * pb.npw_max)), dim3(256), 0, s, g.p, sh.boxidx.p,
-                           sh.npw.p, nb, pb.npw_max, t0, nt, 1.0 / double(NR), sh.out.p, NR);
+                           sh.npw.p, nbt, pb.npw_max, t0, nt, 1.0 / double(NR), ts ? ts->out : sh.out.p, NR);
       });
     }
     TC_HIP(hipEventRecord(ev.e[4], s));
 
     // ---- 5: kinetic energy and FP64 corrections
     K(TC_K_CORR, 0.0, [&] {
-      hipLaunchKernelGGL(k_kinetic, dim3(P), dim3(256), 0, s, bitc ? sh.coefL.p : sh.coef.p, sh.coef.p, sh.kg.p,
-                         sh.npw.p, nb, pb.npw_max, sh.tkin.p);
-      TC_HIP(hipMemsetAsync(sh.ecorr.p, 0, size_t(2) * P * sizeof(double), s));
-      if (pb.div && (pb.mask & TC_T_CORR) && (m.m2ax || m.m3a2 || m.m3b6)) corrections(s, sh, pb, m);
+      if (!ts) {
+        hipLaunchKernelGGL(k_kinetic, dim3(P), dim3(256), 0, s, bitc ? sh.coefL.p : sh.coef.p, sh.coef.p, sh.kg.p,
+                           sh.npw.p, nb, pb.npw_max, sh.tkin.p);
+        TC_HIP(hipMemsetAsync(sh.ecorr.p, 0, size_t(2) * P * sizeof(double), s));
+      }
+      if (pb.div && (pb.mask & TC_T_CORR) && (m.m2ax || m.m3a2 || m.m3b6)) corrections(s, sh, pb, m, ts);
     });
     TC_HIP(hipEventRecord(ev.e[5], s));
     TC_HIP(hipEventSynchronize(ev.e[5]));
@@ -1269,12 +1311,14 @@ struct EngineT : Engine {
   // SCF-mesh divergence corrections in FP64 (2ax, 3a2, 3b6); see k_corr_apply.
   // Biorthogonal mode: overlaps S(a,b) = <chi_a|psi_b>, densities and 3a2 sources with conj(chi),
   // energies with <chi|.
-  void corrections(hipStream_t s, Shared& sh, const Problem& pb, const Masks& m) {
+  // With a target set, the occupied-set quantities are formed the same way and the target-dependent ones
+  // (S(mu, v) = <chi_mu|v>, O(mu, v) = <chi_mu|F1 v>, W_v = FT(F2 v)) from the trial vectors.
+  void corrections(hipStream_t s, Shared& sh, const Problem& pb, const Masks& m, const TargetSet* ts) {
     const int P = pb.P(), nb = pb.nb, nk = pb.nk;
     const bool bitc = pb.bitc;
     const double* cl = bitc ? sh.coefL.p : sh.coef.p;
-    hipLaunchKernelGGL(k_overlap, dim3(nk * nb * nb), dim3(256), 0, s, cl, sh.coef.p, sh.npw.p, nb, pb.npw_max, nk,
-                       sh.S.p);
+    hipLaunchKernelGGL(k_overlap, dim3(nk * nb * nb), dim3(256), 0, s, cl, nb, sh.coef.p, nb, sh.npw.p, pb.npw_max,
+                       nk, sh.S.p);
     std::vector<double> S(size_t(2) * nk * nb * nb);
     TC_HIP(hipMemcpyAsync(S.data(), sh.S.p, S.size() * sizeof(double), hipMemcpyDeviceToHost, s));
     TC_HIP(hipMemcpyAsync(focc.p, pb.occ.data(), P * sizeof(double), hipMemcpyHostToDevice, s));
@@ -1309,8 +1353,8 @@ struct EngineT : Engine {
     hipLaunchKernelGGL((k_gather<double>), dim3(nblk(long(P) * pb.npw_max)), dim3(256), 0, s,
                        prod64.p + size_t(P) * NR, sh.boxidx.p, sh.npw.p, nb, pb.npw_max, 0, P, 1.0 / double(NR),
                        sh.Wg.p, NR);
-    hipLaunchKernelGGL(k_overlap, dim3(nk * nb * nb), dim3(256), 0, s, cl, sh.Zg.p, sh.npw.p, nb, pb.npw_max, nk,
-                       sh.O.p);
+    hipLaunchKernelGGL(k_overlap, dim3(nk * nb * nb), dim3(256), 0, s, cl, nb, sh.Zg.p, nb, sh.npw.p, pb.npw_max,
+                       nk, sh.O.p);
     TC_HIP(hipStreamSynchronize(s));
     // scalars: n~(0) per spin and const1 of the G = G' = 0 correction of 3a2
     double n0 = 0, n0i = 0;   // n~(0) = sum_a w_a S(a,a) / Omega (real in TC mode)
@@ -1335,11 +1379,46 @@ struct EngineT : Engine {
           const1 += fab * re;
           if (bitc) const1i += fab * (sab[0] * sba[1] + sab[1] * sba[0]);
         }
-    hipLaunchKernelGGL(k_corr_apply, dim3(nblk(long(P) * pb.npw_max)), dim3(256), 0, s, sh.coef.p, sh.S.p, sh.O.p,
-                       sh.Zg.p, sh.Wg.p, focc.p, sh.npw.p, nb, pb.npw_max, P, pb.omega, m.m2ax, pb.delta_gb, m.m3a2,
-                       const1, const1i, m.m3b6, c1s * n0, c1s * n0i, sh.dhc2.p, sh.dhc3.p);
-    hipLaunchKernelGGL(k_corr_add, dim3(P), dim3(256), 0, s, cl, sh.dhc2.p, sh.dhc3.p, sh.npw.p, nb, pb.npw_max,
-                       sh.out.p, sh.ecorr.p);
+    if (!ts) {
+      hipLaunchKernelGGL(k_corr_apply, dim3(nblk(long(P) * pb.npw_max)), dim3(256), 0, s, sh.coef.p, sh.coef.p,
+                         sh.S.p, sh.O.p, sh.Zg.p, sh.Wg.p, focc.p, sh.npw.p, nb, nb, pb.npw_max, P, pb.omega, m.m2ax,
+                         pb.delta_gb, m.m3a2, const1, const1i, m.m3b6, c1s * n0, c1s * n0i, sh.dhc2.p, sh.dhc3.p);
+      hipLaunchKernelGGL(k_corr_add, dim3(P), dim3(256), 0, s, cl, sh.dhc2.p, sh.dhc3.p, sh.npw.p, nb, pb.npw_max,
+                         sh.out.p, sh.ecorr.p);
+      return;
+    }
+    // target set: FP64 fields of the trial vectors, F1 v and F2 v, overlaps with the left occupied set
+    const int nv = ts->nvec, NT = nk * nv;
+    const size_t nc = size_t(2) * NT * pb.npw_max;
+    psiT64.alloc(size_t(NT) * NR);
+    prodT.alloc(size_t(2) * NT * NR);
+    sh.ZgT.alloc(nc);
+    sh.WgT.alloc(nc);
+    sh.dhc2T.alloc(nc);
+    sh.dhc3T.alloc(nc);
+    sh.ST.alloc(size_t(2) * nk * nb * nv);
+    sh.OT.alloc(size_t(2) * nk * nb * nv);
+    sh.ecorrT.alloc(size_t(2) * NT);
+    TC_HIP(hipMemsetAsync(psiT64.p, 0, size_t(NT) * NR * sizeof(cx<double>), s));
+    hipLaunchKernelGGL((k_scatter<double>), dim3(nblk(long(NT) * pb.npw_max)), dim3(256), 0, s, ts->coef, sh.boxidx.p,
+                       sh.npw.p, sh.kg.p, nv, pb.npw_max, NT, -1, psiT64.p, NR);
+    fft3d_t<double, N>(psiT64.p, NT, +1, s);
+    hipLaunchKernelGGL((k_corr_products<N>), dim3(nblk(2L * NT * NR)), dim3(256), 0, s, F1, psiT64.p, NT, prodT.p);
+    fft3d_t<double, N>(prodT.p, 2L * NT, -1, s);
+    hipLaunchKernelGGL((k_gather<double>), dim3(nblk(long(NT) * pb.npw_max)), dim3(256), 0, s, prodT.p, sh.boxidx.p,
+                       sh.npw.p, nv, pb.npw_max, 0, NT, 1.0 / double(NR), sh.ZgT.p, NR);
+    hipLaunchKernelGGL((k_gather<double>), dim3(nblk(long(NT) * pb.npw_max)), dim3(256), 0, s,
+                       prodT.p + size_t(NT) * NR, sh.boxidx.p, sh.npw.p, nv, pb.npw_max, 0, NT, 1.0 / double(NR),
+                       sh.WgT.p, NR);
+    hipLaunchKernelGGL(k_overlap, dim3(nk * nb * nv), dim3(256), 0, s, cl, nb, ts->coef, nv, sh.npw.p, pb.npw_max, nk,
+                       sh.ST.p);
+    hipLaunchKernelGGL(k_overlap, dim3(nk * nb * nv), dim3(256), 0, s, cl, nb, sh.ZgT.p, nv, sh.npw.p, pb.npw_max, nk,
+                       sh.OT.p);
+    hipLaunchKernelGGL(k_corr_apply, dim3(nblk(long(NT) * pb.npw_max)), dim3(256), 0, s, ts->coef, sh.coef.p, sh.ST.p,
+                       sh.OT.p, sh.Zg.p, sh.WgT.p, focc.p, sh.npw.p, nb, nv, pb.npw_max, NT, pb.omega, m.m2ax,
+                       pb.delta_gb, m.m3a2, const1, const1i, m.m3b6, c1s * n0, c1s * n0i, sh.dhc2T.p, sh.dhc3T.p);
+    hipLaunchKernelGGL(k_corr_add, dim3(NT), dim3(256), 0, s, ts->coef, sh.dhc2T.p, sh.dhc3T.p, sh.npw.p, nv,
+                       pb.npw_max, ts->out, sh.ecorrT.p);
   }
 };
 
@@ -1401,6 +1480,7 @@ struct tc_ctx {
   std::vector<double> hcoef;   // [P][npw_max] complex staging
   double e_total = 0, e_parts[TC_E_NPARTS] = {0, 0, 0, 0};
   std::vector<double> eps;   // [P] complex orbital energies of the last application
+  DBuf<double> coefT, outT;  // host-buffer tc_apply staging
   double stage_ms[6] = {0, 0, 0, 0, 0, 0};
   double total_ms = 0;
   Prof prof;
@@ -1495,7 +1575,7 @@ void finish_energy(tc_ctx* c) {
 }
 
 // One application with whatever tables are uploaded; energies kept for tc_energy.
-void run_apply(tc_ctx* c, void* out_dev, double* out_host) {
+void alloc_shared(tc_ctx* c) {
   Problem& pb = c->pb;
   Shared& sh = c->sh;
   const int P = pb.P();
@@ -1510,6 +1590,13 @@ void run_apply(tc_ctx* c, void* out_dev, double* out_host) {
   sh.S.alloc(size_t(2) * pb.nk * pb.nb * pb.nb);
   sh.O.alloc(size_t(2) * pb.nk * pb.nb * pb.nb);
   sh.eps.alloc(size_t(2) * P);
+}
+
+void run_apply(tc_ctx* c, void* out_dev, double* out_host) {
+  Problem& pb = c->pb;
+  Shared& sh = c->sh;
+  const int P = pb.P();
+  alloc_shared(c);
   c->eng->prof = &c->prof;
   c->eng->apply(c->stream, sh, pb, c->stage_ms);
   c->total_ms = 0;
@@ -1533,6 +1620,23 @@ int do_apply(tc_ctx* c, void* out_dev, double* out_host) {
   int st = prepare(c);
   if (st != TC_OK) return st;
   run_apply(c, out_dev, out_host);
+  return TC_OK;
+}
+
+// The operator of the loaded orbitals applied to nvec trial vectors per k-point (device in/out).
+int do_apply_vectors(tc_ctx* c, int nvec, const double* in_dev, double* out_dev) {
+  if (nvec <= 0) return fail(c, TC_ERR_ARG, "nvec must be positive");
+  int st = prepare(c);
+  if (st != TC_OK) return st;
+  alloc_shared(c);
+  TargetSet ts;
+  ts.coef = in_dev;
+  ts.nvec = nvec;
+  ts.out = out_dev;
+  double stage[6];
+  c->eng->prof = &c->prof;
+  c->eng->apply(c->stream, c->sh, c->pb, stage, &ts);
+  TC_HIP(hipStreamSynchronize(c->stream));
   return TC_OK;
 }
 
@@ -1684,8 +1788,8 @@ int biorthogonalize(tc_ctx* c, int ik) {
   hipStream_t s = c->stream;
   TC_HIP(hipMemsetAsync(sh.bo_flag.p, 0, sizeof(int), s));
   hipLaunchKernelGGL(k_bo_normalize, dim3(nb), dim3(256), 0, s, sh.coef.p + off, npw, npm, sh.bo_flag.p);
-  hipLaunchKernelGGL(k_overlap, dim3(nb * nb), dim3(256), 0, s, sh.bo_l.p, sh.coef.p + off, sh.npw.p + ik, nb, npm, 1,
-                     sh.bo_s.p);
+  hipLaunchKernelGGL(k_overlap, dim3(nb * nb), dim3(256), 0, s, sh.bo_l.p, nb, sh.coef.p + off, nb, sh.npw.p + ik,
+                     npm, 1, sh.bo_s.p);
   hipLaunchKernelGGL(k_bo_invert, dim3(1), dim3(256), 0, s, sh.bo_s.p, nb, sh.bo_aug.p, sh.bo_inv.p, sh.bo_flag.p);
   int flag = 0;
   TC_HIP(hipMemcpyAsync(&flag, sh.bo_flag.p, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -1902,6 +2006,30 @@ int tc_apply_all(tc_ctx* c, double* out) {
 
 int tc_apply_all_dev(tc_ctx* c, void* out_dev) {
   return guard(c, [&]() -> int { return do_apply(c, out_dev, nullptr); });
+}
+
+int tc_apply(tc_ctx* c, int nvec, const double* in, double* out) {
+  return guard(c, [&]() -> int {
+    if (!in || !out) return fail(c, TC_ERR_ARG, "null vectors");
+    if (nvec <= 0) return fail(c, TC_ERR_ARG, "nvec must be positive");
+    int st = prepare(c);
+    if (st != TC_OK) return st;
+    const size_t n = size_t(2) * c->pb.nk * nvec * c->pb.npw_max;
+    c->coefT.alloc(n);
+    c->outT.alloc(n);
+    TC_HIP(hipMemcpy(c->coefT.p, in, n * sizeof(double), hipMemcpyHostToDevice));
+    st = do_apply_vectors(c, nvec, c->coefT.p, c->outT.p);
+    if (st != TC_OK) return st;
+    TC_HIP(hipMemcpy(out, c->outT.p, n * sizeof(double), hipMemcpyDeviceToHost));
+    return TC_OK;
+  });
+}
+
+int tc_apply_dev(tc_ctx* c, int nvec, const void* in_dev, void* out_dev) {
+  return guard(c, [&]() -> int {
+    if (!in_dev || !out_dev) return fail(c, TC_ERR_ARG, "null vectors");
+    return do_apply_vectors(c, nvec, static_cast<const double*>(in_dev), static_cast<double*>(out_dev));
+  });
 }
 
 int tc_orbital_energies(tc_ctx* c, double* eps) {

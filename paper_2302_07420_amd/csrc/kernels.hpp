@@ -22,8 +22,9 @@ struct Recip {
 
 struct MeshInfo {
   int n1, n2, n3;   // k-mesh
-  int nb;           // bands per k-point
+  int nb;           // bands per k-point of the occupied (partner) set
   int P;            // orbitals of one spin channel (nk * nb)
+  int nbt;          // vectors per k-point of the target set (nb when the targets are the orbitals)
 };
 
 __device__ __forceinline__ int kindex_delta(const MeshInfo& mi, int kto, int kfrom) {
@@ -268,9 +269,10 @@ struct FusedArgs {
   int P, T, t0, S, chunk;     // orbitals, targets in batch, first target, partner chunks, partners per chunk
 };
 
-// index of the pair's shift in the kernel tables: k_jt - k_q (sign 1, target passes) or k_q - k_jt (sign 0)
+// index of the pair's shift in the kernel tables: k_jt - k_q (sign 1, target passes) or k_q - k_jt (sign 0);
+// target jt sits at k-point jt / nbt, partner q at q / nb
 __device__ __forceinline__ int pair_dindex(const MeshInfo& mi, int jt, int q, int sign) {
-  const int kt = jt / mi.nb, kq = q / mi.nb;
+  const int kt = jt / mi.nbt, kq = q / mi.nb;
   return sign ? kindex_delta(mi, kt, kq) : kindex_delta(mi, kq, kt);
 }
 
