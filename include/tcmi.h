@@ -174,6 +174,41 @@ int tc_apply(tc_ctx* ctx, int nvec, const double* in, double* out);
 /* Same, with caller-owned device buffers of the same layout.  Synchronous. */
 int tc_apply_dev(tc_ctx* ctx, int nvec, const void* in_dev, void* out_dev);
 
+/* Parameters of the self-consistent loop (Sec. 2.4). */
+typedef struct {
+  int max_iter;   /* iterations (one block-Davidson subspace diagonalisation each), >= 1            */
+  int pmax;       /* expansion blocks per iteration: subspace of (pmax + 1) nband vectors per k,
+                     0..16, at most 512 vectors                                                    */
+  double etol;    /* stop when the energy per cell changes by less than etol (hartree), > 0        */
+  double mix;     /* density-matrix mixing ratio beta in (0, 1]; 1 = no mixing                       */
+  double otol;    /* and when no new orbital has a component above otol outside the span of the
+                     previous ones (<= 0: the energy criterion alone)                               */
+} tc_scf_params;
+
+/* Block-Davidson TC-SCF (TC mode) or BITC-SCF (left orbitals loaded) from the loaded orbitals
+ * (Sec. 2.4, Eq. blockDavid).  Each iteration starts the subspace with the current right orbitals
+ * (orthonormalised) and adds pmax blocks of residuals (h - eps_i) v preconditioned with the function of
+ * Payne et al., with Gram-Schmidt, dropping vectors of norm below 1e-8 or linearly dependent ones.  It
+ * diagonalises the subspace matrix <v_a| T + h |v_b> (FP64, on the device) and takes the nband
+ * eigenvectors of lowest real eigenvalue as the new orbitals: Gram-Schmidt orthonormalised in TC mode;
+ * right and left eigenvectors, biorthonormalised as in tc_load_orbitals, in BITC mode.  The operator is
+ * updated every iteration, with the fillings kept: built from the new orbitals, or with mix < 1 from
+ * the new orbitals with fillings mix f together with the previous iteration's orbitals, as extra
+ * bands, with fillings (1 - mix) f (density-matrix mixing of Sec. 2.4; the energy of an iteration is
+ * that of this set).  energies (may be NULL)
+ * receives the energy per cell after each iteration; iterations (may be NULL) the number run.  The
+ * loop stops at max_iter, or once the energy changes by less than etol and (otol > 0) the orbitals
+ * move out of their previous span by less than otol (TC energies are not stationary in the orbitals,
+ * so a small energy change alone does not bound the orbitals' error).  The
+ * context then holds the final orbitals alone (tc_get_orbitals) and their energies.
+ * Errors: TC_ERR_ARG for parameters out of range or fewer independent trial vectors than bands;
+ * TC_ERR_DEVICE if the subspace eigensolver does not converge. */
+int tc_scf(tc_ctx* ctx, const tc_scf_params* prm, double* energies, int* iterations);
+
+/* Copy the current orbitals of k-point ik to the host ([nband][npw(ik)] complex128): right (may be
+ * NULL) and, in the biorthogonal mode, left (NULL, or TC_ERR_STATE without left orbitals). */
+int tc_get_orbitals(tc_ctx* ctx, int ik, double* right, double* left);
+
 /* Orbital energies of the last application (runs one if needed): eps receives [nk][nband]
  * complex128, eps_j = <chi_j| T + h2 + h3 |phi_j> with the selected terms and corrections (the
  * diagonal elements of Eqs. SCF / BITCSCF, chi = phi in TC mode; Re eps_jj is the one-electron

@@ -41,6 +41,12 @@ class TCError(RuntimeError):
     pass
 
 
+class SCFParams(ctypes.Structure):
+    """tc_scf_params of include/tcmi.h."""
+    _fields_ = [("max_iter", ctypes.c_int), ("pmax", ctypes.c_int), ("etol", ctypes.c_double),
+                ("mix", ctypes.c_double), ("otol", ctypes.c_double)]
+
+
 def lib():
     """Load libtcmi.so (raises if it has not been built)."""
     global _lib
@@ -64,6 +70,8 @@ def lib():
         "tc_load_orbitals": (I, [P, I, I, dp, dp, dp]),
         "tc_orbital_energies": (I, [P, dp]),
         "tc_apply": (I, [P, I, dp, dp]),
+        "tc_scf": (I, [P, ctypes.POINTER(SCFParams), dp, ctypes.POINTER(I)]),
+        "tc_get_orbitals": (I, [P, I, dp, dp]),
         "tc_apply_dev": (I, [P, I, P, P]),
         "tc_load_orbitals_dev": (I, [P, I, I, P, dp]),
         "tc_apply_all": (I, [P, dp]),
@@ -209,6 +217,22 @@ class TCOperator:
         """Device form of apply_vectors: [nk][nvec][npw_max] complex128 buffers (synchronous)."""
         self._check(self._L.tc_apply_dev(self._h, int(nvec), ctypes.c_void_p(in_ptr), ctypes.c_void_p(out_ptr)),
                     "tc_apply_dev")
+
+    def scf(self, max_iter=50, pmax=2, etol=1e-10, mix=1.0, otol=1e-8):
+        """Block-Davidson TC / BITC self-consistent loop; returns (energies per iteration, iterations)."""
+        prm = SCFParams(int(max_iter), int(pmax), float(etol), float(mix), float(otol))
+        e = np.zeros(max(1, int(max_iter)))
+        n = ctypes.c_int(0)
+        self._check(self._L.tc_scf(self._h, ctypes.byref(prm), _dp(e), ctypes.byref(n)), "tc_scf")
+        return e[: n.value].copy(), n.value
+
+    def get_orbitals(self, ik, left=False):
+        """Current orbitals of k-point ik: right (nband, npw), and left too when ``left``."""
+        r = np.zeros((self.nband, self.npw[ik]), dtype=np.complex128)
+        l = np.zeros_like(r) if left else None
+        self._check(self._L.tc_get_orbitals(self._h, int(ik), _dp(r.view(np.float64)),
+                                            _dp(l.view(np.float64)) if left else None), "tc_get_orbitals")
+        return (r, l) if left else r
 
     def orbital_energies(self) -> np.ndarray:
         """Complex eps_j = <chi_j| T + h |phi_j> per orbital of the last application, shape [nk, nband]."""

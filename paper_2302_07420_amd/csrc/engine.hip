@@ -23,6 +23,7 @@
 
 #include "../../include/tcmi.h"
 #include "kernels.hpp"
+#include "scf.hpp"
 
 using namespace tcmi;
 
@@ -1481,6 +1482,9 @@ struct tc_ctx {
   double e_total = 0, e_parts[TC_E_NPARTS] = {0, 0, 0, 0};
   std::vector<double> eps;   // [P] complex orbital energies of the last application
   DBuf<double> coefT, outT;  // host-buffer tc_apply staging
+  // block-Davidson self-consistent loop
+  DBuf<double> dV, dHV, dHs, dwork, dX, dY, deval, deps, dcur, dold, dnew, dmix, dchange;
+  DBuf<int> dvalid, dstatus;
   double stage_ms[6] = {0, 0, 0, 0, 0, 0};
   double total_ms = 0;
   Prof prof;
@@ -1775,21 +1779,21 @@ int begin_load(tc_ctx* c, int ik, int nband, const double* occ) {
 // FP64 biorthogonalisation of k-point ik on the device (see k_bo_normalize / k_bo_invert / k_bo_left):
 // the right coefficients in sh.coef are normalised in place, the left ones (staged in sh.bo_l) are
 // written to sh.coefL.
-int biorthogonalize(tc_ctx* c, int ik) {
+// Same for nb bands of k-point ik held elsewhere: right (normalised in place), the left set staged in
+// sh.bo_l, the biorthogonalised left set written to lout.
+int biorthogonalize_at(tc_ctx* c, int ik, int nb, double* right, double* lout) {
   Problem& pb = c->pb;
   Shared& sh = c->sh;
-  const int nb = pb.nb, npw = pb.npw[ik], npm = pb.npw_max;
-  const size_t off = size_t(2) * ik * nb * npm;
-  sh.coefL.alloc(size_t(2) * pb.P() * npm);
+  const int npw = pb.npw[ik], npm = pb.npw_max;
   sh.bo_s.alloc(size_t(2) * nb * nb);
   sh.bo_inv.alloc(size_t(2) * nb * nb);
   sh.bo_aug.alloc(size_t(2) * (size_t(nb) * 2 * nb + nb));
   sh.bo_flag.alloc(1);
   hipStream_t s = c->stream;
   TC_HIP(hipMemsetAsync(sh.bo_flag.p, 0, sizeof(int), s));
-  hipLaunchKernelGGL(k_bo_normalize, dim3(nb), dim3(256), 0, s, sh.coef.p + off, npw, npm, sh.bo_flag.p);
-  hipLaunchKernelGGL(k_overlap, dim3(nb * nb), dim3(256), 0, s, sh.bo_l.p, nb, sh.coef.p + off, nb, sh.npw.p + ik,
-                     npm, 1, sh.bo_s.p);
+  hipLaunchKernelGGL(k_bo_normalize, dim3(nb), dim3(256), 0, s, right, npw, npm, sh.bo_flag.p);
+  hipLaunchKernelGGL(k_overlap, dim3(nb * nb), dim3(256), 0, s, sh.bo_l.p, nb, right, nb, sh.npw.p + ik, npm, 1,
+                     sh.bo_s.p);
   hipLaunchKernelGGL(k_bo_invert, dim3(1), dim3(256), 0, s, sh.bo_s.p, nb, sh.bo_aug.p, sh.bo_inv.p, sh.bo_flag.p);
   int flag = 0;
   TC_HIP(hipMemcpyAsync(&flag, sh.bo_flag.p, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -1798,8 +1802,180 @@ int biorthogonalize(tc_ctx* c, int ik) {
   if (flag == 2)
     return fail(c, TC_ERR_ARG, "the left/right overlap of k-point " + std::to_string(ik) + " is singular");
   hipLaunchKernelGGL(k_bo_left, dim3(nblk(long(nb) * npm)), dim3(256), 0, s, sh.bo_inv.p, sh.bo_l.p, nb, npw, npm,
-                     sh.coefL.p + off);
+                     lout);
   TC_HIP(hipStreamSynchronize(s));
+  return TC_OK;
+}
+
+int biorthogonalize(tc_ctx* c, int ik) {
+  Problem& pb = c->pb;
+  const size_t off = size_t(2) * ik * pb.nb * pb.npw_max;
+  c->sh.coefL.alloc(size_t(2) * pb.P() * pb.npw_max);
+  return biorthogonalize_at(c, ik, pb.nb, c->sh.coef.p + off, c->sh.coefL.p + off);
+}
+
+// Replace the context's orbital set by nbx bands per k-point from device buffers ([nk][nbx][npw_max]
+// complex128; left may be null) with fillings occ ([nk][nbx]).
+void load_set(tc_ctx* c, const double* r, const double* l, int nbx, const std::vector<double>& occ) {
+  Problem& pb = c->pb;
+  pb.nb = nbx;
+  pb.occ = occ;
+  std::fill(pb.loaded.begin(), pb.loaded.end(), 1);
+  std::fill(pb.left.begin(), pb.left.end(), l ? 1 : 0);
+  const size_t n = size_t(2) * pb.P() * pb.npw_max;
+  c->sh.coef.alloc(n);
+  TC_HIP(hipMemcpyAsync(c->sh.coef.p, r, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  if (l) {
+    c->sh.coefL.alloc(n);
+    TC_HIP(hipMemcpyAsync(c->sh.coefL.p, l, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  }
+  TC_HIP(hipStreamSynchronize(c->stream));
+  upload_basis_data(c);
+  c->have_result = false;
+}
+
+// Block-Davidson TC / BITC self-consistent loop (Sec. 2.4).  Each iteration: the current right orbitals,
+// orthonormalised, start the subspace; pmax blocks of Payne-preconditioned residuals
+// P (h - eps_i) v_{(p-1) nb + i} are added with Gram-Schmidt (dropping negligible or dependent vectors);
+// the subspace matrix <v_a|T + h|v_b> is diagonalised and the nb eigenvectors of lowest real eigenvalue
+// become the new orbitals (TC: Gram-Schmidt orthonormalised; BITC: right and left eigenvectors, then
+// biorthonormalised), so the operator is updated every loop.  The loop ends when the energy changes by
+// less than etol.
+int do_scf(tc_ctx* c, const tc_scf_params& prm, double* ehist, int* niter) {
+  if (prm.max_iter < 1 || prm.pmax < 0 || prm.pmax > 16 || !(prm.etol > 0) || !(prm.mix > 0 && prm.mix <= 1))
+    return fail(c, TC_ERR_ARG,
+                "scf parameters out of range (max_iter >= 1, 0 <= pmax <= 16, etol > 0, 0 < mix <= 1)");
+  int st = prepare(c);
+  if (st != TC_OK) return st;
+  Problem& pb = c->pb;
+  Shared& sh = c->sh;
+  hipStream_t s = c->stream;
+  const bool bitc = pb.bitc;
+  const int nk = pb.nk, nb = pb.nb, npm = pb.npw_max, P = pb.P();
+  const int nblk_sub = prm.pmax + 1, M = nblk_sub * nb;
+  if (M > 512) return fail(c, TC_ERR_UNSUPPORTED, "subspace larger than 512 vectors per k-point");
+  const std::vector<double> f = pb.occ;        // fillings of the orbitals, [nk][nb]
+  const size_t blk = size_t(2) * P * npm;      // doubles per block of nb bands on every k-point
+  const size_t kb = size_t(2) * nb * npm;      // doubles per k-point within a block
+  c->dV.alloc(nblk_sub * blk);
+  c->dHV.alloc(nblk_sub * blk);
+  c->dHs.alloc(size_t(2) * nk * M * M);
+  c->dwork.alloc(size_t(2) * nk * (4 * size_t(M) * M + 2 * M));
+  c->dX.alloc(size_t(2) * nk * M * nb);
+  c->dY.alloc(size_t(2) * nk * M * nb);
+  c->deval.alloc(size_t(2) * P);
+  c->deps.alloc(size_t(2) * P);
+  c->dvalid.alloc(size_t(nk) * M);
+  c->dstatus.alloc(nk);
+  c->dchange.alloc(nk);
+  // current / previous orbitals of the loop (right and left), and the mixed operator set
+  c->dcur.alloc(2 * blk);
+  c->dold.alloc(2 * blk);
+  c->dnew.alloc(2 * blk);
+  c->dmix.alloc(4 * blk);
+  double* cur_r = c->dcur.p;
+  double* cur_l = c->dcur.p + blk;
+  double* old_r = c->dold.p;
+  double* old_l = c->dold.p + blk;
+  double* new_r = c->dnew.p;
+  double* new_l = c->dnew.p + blk;
+  double* mix_r = c->dmix.p;
+  double* mix_l = c->dmix.p + 2 * blk;
+  TC_HIP(hipMemcpyAsync(cur_r, sh.coef.p, blk * sizeof(double), hipMemcpyDeviceToDevice, s));
+  if (bitc) TC_HIP(hipMemcpyAsync(cur_l, sh.coefL.p, blk * sizeof(double), hipMemcpyDeviceToDevice, s));
+  const double atol = 1e-8, rtol = 1e-8;
+  double eprev = 0;
+  int it = 0;
+  bool mixed = false;
+  for (; it < prm.max_iter; ++it) {
+    TC_HIP(hipMemcpyAsync(c->dV.p, cur_r, blk * sizeof(double), hipMemcpyDeviceToDevice, s));
+    TC_HIP(hipMemsetAsync(c->dvalid.p, 0, size_t(nk) * M * sizeof(int), s));
+    hipLaunchKernelGGL(k_gram_schmidt, dim3(nk), dim3(256), 0, s, c->dV.p, c->dvalid.p, sh.npw.p, nk, nb, npm, M, 0,
+                       nb, atol, rtol);
+    for (int p = 0; p < nblk_sub; ++p) {
+      if (p > 0) {
+        hipLaunchKernelGGL(k_precond_residual, dim3(P), dim3(256), 0, s, c->dV.p, c->dHV.p, c->deps.p, sh.kg.p,
+                           sh.npw.p, nk, nb, npm, p, atol);
+        hipLaunchKernelGGL(k_gram_schmidt, dim3(nk), dim3(256), 0, s, c->dV.p, c->dvalid.p, sh.npw.p, nk, nb, npm,
+                           M, p * nb, (p + 1) * nb, 0.0, rtol);
+      }
+      st = do_apply_vectors(c, nb, c->dV.p + p * blk, c->dHV.p + p * blk);
+      if (st != TC_OK) return st;
+      hipLaunchKernelGGL(k_add_kinetic, dim3(nblk(long(P) * npm)), dim3(256), 0, s, c->dV.p, c->dHV.p, sh.kg.p,
+                         sh.npw.p, nk, nb, npm, p);
+      if (p == 0)
+        hipLaunchKernelGGL(k_rayleigh, dim3(P), dim3(256), 0, s, c->dV.p, c->dHV.p, sh.npw.p, nk, nb, npm,
+                           c->deps.p);
+    }
+    hipLaunchKernelGGL(k_subspace_matrix, dim3(nk * M * M), dim3(256), 0, s, c->dV.p, c->dHV.p, sh.npw.p, nk, nb,
+                       npm, M, c->dHs.p);
+    hipLaunchKernelGGL(k_subspace_eig, dim3((nk + 63) / 64), dim3(64), 0, s, c->dHs.p, c->dvalid.p, nk, nb, M,
+                       c->dwork.p, c->dX.p, c->dY.p, c->deval.p, c->dstatus.p, c->dchange.p);
+    std::vector<int> status(nk);
+    std::vector<double> change(nk);
+    TC_HIP(hipMemcpyAsync(status.data(), c->dstatus.p, nk * sizeof(int), hipMemcpyDeviceToHost, s));
+    TC_HIP(hipMemcpyAsync(change.data(), c->dchange.p, nk * sizeof(double), hipMemcpyDeviceToHost, s));
+    TC_HIP(hipStreamSynchronize(s));
+    double dmax = 0;
+    for (int k = 0; k < nk; ++k) {
+      if (status[k] == 1) return fail(c, TC_ERR_DEVICE, "subspace eigensolver did not converge");
+      if (status[k] == 2) return fail(c, TC_ERR_ARG, "fewer independent trial vectors than bands");
+      dmax = std::max(dmax, change[k]);
+    }
+    hipLaunchKernelGGL(k_subspace_combine, dim3(nblk(long(P) * npm)), dim3(256), 0, s, c->dV.p, c->dX.p, nk, nb,
+                       npm, M, new_r);
+    if (!bitc) {
+      TC_HIP(hipMemsetAsync(c->dvalid.p, 0, size_t(nk) * M * sizeof(int), s));
+      hipLaunchKernelGGL(k_gram_schmidt, dim3(nk), dim3(256), 0, s, new_r, c->dvalid.p, sh.npw.p, nk, nb, npm, M, 0,
+                         nb, 0.0, 0.0);
+    } else {
+      hipLaunchKernelGGL(k_subspace_combine, dim3(nblk(long(P) * npm)), dim3(256), 0, s, c->dV.p, c->dY.p, nk, nb,
+                         npm, M, new_l);
+      sh.bo_l.alloc(kb);
+      for (int k = 0; k < nk; ++k) {
+        TC_HIP(hipMemcpyAsync(sh.bo_l.p, new_l + k * kb, kb * sizeof(double), hipMemcpyDeviceToDevice, s));
+        st = biorthogonalize_at(c, k, nb, new_r + k * kb, new_l + k * kb);
+        if (st != TC_OK) return st;
+      }
+    }
+    // previous <- current <- new
+    TC_HIP(hipMemcpyAsync(c->dold.p, c->dcur.p, 2 * blk * sizeof(double), hipMemcpyDeviceToDevice, s));
+    TC_HIP(hipMemcpyAsync(c->dcur.p, c->dnew.p, 2 * blk * sizeof(double), hipMemcpyDeviceToDevice, s));
+    // operator of the next iteration: the new orbitals, or with mixing beta the new orbitals (beta f) and
+    // the previous ones ((1 - beta) f) as extra bands (density-matrix mixing, Sec. 2.4)
+    if (prm.mix < 1.0) {
+      std::vector<double> fm(size_t(2) * P);
+      for (int k = 0; k < nk; ++k)
+        for (int side = 0; side < (bitc ? 2 : 1); ++side) {
+          double* dst = side ? mix_l : mix_r;
+          TC_HIP(hipMemcpyAsync(dst + 2 * k * kb, (side ? cur_l : cur_r) + k * kb, kb * sizeof(double),
+                                hipMemcpyDeviceToDevice, s));
+          TC_HIP(hipMemcpyAsync(dst + (2 * k + 1) * kb, (side ? old_l : old_r) + k * kb, kb * sizeof(double),
+                                hipMemcpyDeviceToDevice, s));
+        }
+      for (int k = 0; k < nk; ++k)
+        for (int i = 0; i < nb; ++i) {
+          fm[size_t(k) * 2 * nb + i] = prm.mix * f[size_t(k) * nb + i];
+          fm[size_t(k) * 2 * nb + nb + i] = (1.0 - prm.mix) * f[size_t(k) * nb + i];
+        }
+      load_set(c, mix_r, bitc ? mix_l : nullptr, 2 * nb, fm);
+      mixed = true;
+    } else {
+      load_set(c, cur_r, bitc ? cur_l : nullptr, nb, f);
+    }
+    run_apply(c, nullptr, nullptr);
+    if (ehist) ehist[it] = c->e_total;
+    if (it > 0 && std::fabs(c->e_total - eprev) < prm.etol && (prm.otol <= 0 || dmax < prm.otol)) {
+      ++it;
+      break;
+    }
+    eprev = c->e_total;
+  }
+  if (mixed) {   // the context ends with the loop's orbitals alone and their energies
+    load_set(c, cur_r, bitc ? cur_l : nullptr, nb, f);
+    run_apply(c, nullptr, nullptr);
+  }
+  if (niter) *niter = it;
   return TC_OK;
 }
 
@@ -2006,6 +2182,33 @@ int tc_apply_all(tc_ctx* c, double* out) {
 
 int tc_apply_all_dev(tc_ctx* c, void* out_dev) {
   return guard(c, [&]() -> int { return do_apply(c, out_dev, nullptr); });
+}
+
+int tc_scf(tc_ctx* c, const tc_scf_params* prm, double* energies, int* iterations) {
+  return guard(c, [&]() -> int {
+    if (!prm) return fail(c, TC_ERR_ARG, "null parameters");
+    return do_scf(c, *prm, energies, iterations);
+  });
+}
+
+int tc_get_orbitals(tc_ctx* c, int ik, double* right, double* left) {
+  return guard(c, [&]() -> int {
+    Problem& pb = c->pb;
+    if (ik < 0 || ik >= pb.nk) return fail(c, TC_ERR_ARG, "k-point index out of range");
+    if (!pb.loaded[ik]) return fail(c, TC_ERR_STATE, "orbitals of this k-point are not loaded");
+    if (left && !pb.left[ik]) return fail(c, TC_ERR_STATE, "no left orbitals on this k-point");
+    const int nb = pb.nb, npw = pb.npw[ik], npm = pb.npw_max;
+    std::vector<double> buf(size_t(2) * nb * npm);
+    for (int side = 0; side < 2; ++side) {
+      double* dst = side == 0 ? right : left;
+      if (!dst) continue;
+      const double* src = (side == 0 ? c->sh.coef.p : c->sh.coefL.p) + size_t(2) * ik * nb * npm;
+      TC_HIP(hipMemcpy(buf.data(), src, buf.size() * sizeof(double), hipMemcpyDeviceToHost));
+      for (int b = 0; b < nb; ++b)
+        std::memcpy(dst + size_t(2) * b * npw, &buf[size_t(2) * b * npm], size_t(2) * npw * sizeof(double));
+    }
+    return TC_OK;
+  });
 }
 
 int tc_apply(tc_ctx* c, int nvec, const double* in, double* out) {

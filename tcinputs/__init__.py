@@ -158,6 +158,22 @@ def random_orbitals(lattice, kmesh, ecut, nb, sigma, seed, left_mix=None):
     return mill, right, (left if left_mix is not None else None)
 
 
+def perturbed_start(w, amp, seed, left_amp=None):
+    """An SCF starting point: each k-point's orbitals plus amp times random complex noise on its plane-wave
+    set, orthonormalised (QR); with left_amp, also a left set = right + left_amp noise (biorthogonal mode)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    right, left = [], []
+    for c in w.right:
+        z = rng.standard_normal(c.shape) + 1j * rng.standard_normal(c.shape)
+        q, r = np.linalg.qr((c + amp * z / np.sqrt(c.shape[1])).T)
+        q = q * (np.diag(r) / np.abs(np.diag(r)))[None, :]
+        right.append(np.ascontiguousarray(q.T))
+        if left_amp is not None:
+            z2 = rng.standard_normal(c.shape) + 1j * rng.standard_normal(c.shape)
+            left.append(right[-1] + left_amp * z2 / np.sqrt(c.shape[1]))
+    return w.replace(right=right, left=left if left_amp is not None else None)
+
+
 def grid_fits(miller_list, grid) -> bool:
     """True when every pair density is alias-free: N_i/2 >= 2 max|m_i| + 1."""
     mx = np.max(np.stack([np.max(np.abs(m), axis=0) for m in miller_list]), axis=0)
@@ -170,12 +186,12 @@ def grid_fits(miller_list, grid) -> bool:
 # else is synthetic.
 # --------------------------------------------------------------------------
 
-def heg_gamma(rs=4.0, nelec=14, grid=16, mmax2=9) -> Workload:
-    """Electron gas, 14 electrons, Gamma only: occupied shell |m|^2 <= 1."""
+def heg_gamma(rs=4.0, nelec=14, grid=16, mmax2=9, occ_m2=1) -> Workload:
+    """Electron gas, Gamma only: occupied shell |m|^2 <= occ_m2 (7 plane waves for 14 electrons)."""
     L = (nelec * 4.0 * math.pi / 3.0 * rs ** 3) ** (1.0 / 3.0)
     lat = sc_lattice(L)
     M = miller_norm2(mmax2)
-    occm = miller_norm2(1)                       # 7 plane waves
+    occm = miller_norm2(occ_m2)
     nb = occm.shape[0]
     coef = np.zeros((nb, M.shape[0]), dtype=np.complex128)
     for b, m in enumerate(occm):

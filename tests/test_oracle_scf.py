@@ -1,0 +1,35 @@
+"""Pins of the SCF oracle (O5, exact diagonalisation per iteration) on the electron gas.
+
+Plane waves solve the SCF equation of the electron gas, so from a perturbed start the loop must
+return to the occupied plane waves and the energy of the closed forms (O3), in the TC mode and in the
+biorthogonal mode (which coincides with TC for the electron gas, Sec. 4.2).
+"""
+import numpy as np
+import pytest
+
+import tcinputs as T
+from oracle import scf as S
+from oracle.heg import heg_energy
+
+
+@pytest.fixture(scope="module")
+def heg2():
+    # 2 electrons (one doubly occupied plane wave, m = 0) in the basis |m|^2 <= 1, 8^3 grid
+    return T.heg_gamma(rs=4.0, nelec=2, grid=8, mmax2=1, occ_m2=0)
+
+
+@pytest.mark.parametrize("left_amp", [None, 0.3])
+def test_heg2_returns_to_the_plane_wave(heg2, left_amp):
+    E0, _ = heg_energy(heg2)
+    start = T.perturbed_start(heg2, 0.4, 3, left_amp=left_amp)
+    hist, right, left, evals, Ef = S.scf(start, max_iter=60, etol=1e-14)
+    assert abs(Ef - E0) < 1e-12 * abs(E0) + 1e-14
+    c = right[0][0]
+    assert abs(abs(c[0]) - 1.0) < 1e-6 and np.abs(c[1:]).max() < 1e-6
+    assert abs(hist[0] - E0) > 1e-4                                   # the start was away from it
+
+
+def test_operator_matrix_of_plane_waves_is_diagonal(heg2):
+    H = S.operator_matrices(heg2, heg2.right)[0]
+    off = H - np.diag(np.diag(H))
+    assert np.abs(off).max() < 1e-12 * np.abs(H).max()
