@@ -161,6 +161,7 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 GPU path")
     ap.add_argument("--no-split", action="store_true", help="skip the FP32 + split-BF16 (MFMA z-DFT) path")
     ap.add_argument("--no-bitc", action="store_true", help="skip the biorthogonal-mode side measurement")
+    ap.add_argument("--no-scf", action="store_true", help="skip the block-Davidson SCF side measurement")
     ap.add_argument("--workload", default="fcc_si_k444_g24",
                     help="named workload: fcc_si_k444_g24 (default), heg14_g16, heg54_twist2_g32, fcc_si_x2_k222_g48")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
@@ -233,6 +234,23 @@ def main():
                 "kernels_ms_per_step": {k: v["ms"] / args.steps for k, v in st_b.items() if v["ms"] > 0}}
         log(f"bitc fp32: {ms_b:.2f} ms/step, E = {e_b:.12f}; fp64 {res_b['fp64'][0]:.2f} ms/step")
 
+    scf = None
+    if not args.no_scf and args.workload == "fcc_si_k444_g24":
+        # three block-Davidson iterations (pmax = 2: three applications to 256 trial vectors each, the
+        # subspace diagonalisation, and the energy of the new orbitals) from the workload's orbitals
+        op_c, keep_c = make_op(w, tc.TC_PREC_FP32, stream)
+        op_c.energy()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        hist, nit = op_c.scf(max_iter=3, pmax=2, etol=1e-300, otol=0.0)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        scf = {"iterations": nit, "pmax": 2, "ms_per_iteration": dt / nit * 1e3,
+               "energies_Ha": [float(x) for x in hist], "precision": "fp32"}
+        log(f"scf: {dt / nit * 1e3:.1f} ms per block-Davidson iteration, energies {list(hist)}")
+        op_c.close()
+        del keep_c
+
     # dominant kernel and its roofline (algorithmic bytes / event-timed duration)
     dom = max(stats.items(), key=lambda kv: kv[1]["ms"])
     name, st = dom
@@ -287,6 +305,7 @@ def main():
                                                                   / abs(fp64["energy_Ha"])) if fp64 else None)
         if split else None,
         "bitc_fp32_gpu": bitc,
+        "scf_davidson_gpu": scf,
         "stages_ms": dict(zip(tc.STAGES, stages)),
         "kernels_ms_per_step": per_kernel,
         "kernel_ms_per_step_total": total_kernel_ms,
