@@ -236,8 +236,22 @@ int tc_orbital_energies(tc_ctx* ctx, double* eps);
 int tc_energy_backward(tc_ctx* ctx, double* grad, double dA[2], double dC[2]);
 
 /* Same, writing grad to a caller-owned device buffer of the same layout (may be NULL).
- * Synchronous: returns after the stream has finished the work. */
+ * Synchronous: returns after the stream has finished the work.  With left orbitals loaded a
+ * non-NULL grad is TC_ERR_UNSUPPORTED (use tc_energy_backward_lr); dA and dC are available. */
 int tc_energy_backward_dev(tc_ctx* ctx, void* grad_dev, double dA[2], double dC[2]);
+
+/* Gradients with respect to the right and the left orbitals (host buffers, layout of
+ * tc_energy_backward; each may be NULL), and dA, dC.
+ *  - TC mode: grad_left must be NULL (TC_ERR_ARG); grad_right receives tc_energy_backward's gradient.
+ *  - Biorthogonal mode (Eq. EtotBiTC with the biorthonormal pair held fixed; the
+ *    biorthonormalisation of tc_load_orbitals is not differentiated):
+ *      grad_left  = 2 dE/dchi* = 2 w (T + h) phi        (the operator of Eq. BITCSCF),
+ *      grad_right = 2 dE/dphi* = 2 w (T + h^dagger) chi (the left operator of Eq. BITCSCFconj:
+ *        chi and phi exchanged and v2 replaced by its adjoint, whose grad-u . grad terms change
+ *        sign and whose scalar kernel becomes 4 pi/Q^2 - (grad u)^2~),
+ *    w = f / N_k, one application each.
+ * Term-mask conditions and errors as tc_energy_backward. */
+int tc_energy_backward_lr(tc_ctx* ctx, double* grad_right, double* grad_left, double dA[2], double dC[2]);
 
 /* Wait for all work queued by this context. */
 int tc_sync(tc_ctx* ctx);

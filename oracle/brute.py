@@ -81,21 +81,24 @@ class Brute:
             cl = [np.asarray(c) for c in left]
         elif w.left is not None:
             cl = [np.asarray(c) for c in w.left]
-        # full Bloch orbitals on the cell grid, spin list (unpolarized: same orbitals)
-        phis, chis, grads, ks, fs = [], [], [], [], []
-        for ik in range(self.nk):
-            kg = (self.kfrac[ik][None, :] + w.miller[ik]) @ self.B     # (npw,3)
-            E = np.exp(1j * self.r @ kg.T) / math.sqrt(self.nk * self.omega)  # (Nr,npw)
-            for b in range(cr[ik].shape[0]):
-                phis.append(E @ cr[ik][b])
-                chis.append(E @ (cr[ik][b] if cl is None else cl[ik][b]))
-                grads.append(np.stack([E @ (1j * kg[:, a] * cr[ik][b]) for a in range(3)]))
-                ks.append(ik)
-                fs.append(float(w.occ[ik][b]))
+        # full Bloch orbitals on the cell grid, spin list (unpolarized: the same orbitals in both channels;
+        # polarized input: the down channel's own set, used as given)
+        sets = [(cr, cl, w.occ)]
+        if getattr(w, "right_dn", None) is not None:
+            sets.append(([np.asarray(c) for c in w.right_dn],
+                         None if w.left_dn is None else [np.asarray(c) for c in w.left_dn],
+                         w.occ_dn if w.occ_dn is not None else w.occ))
+        else:
+            sets.append(sets[0])
         self.orbs = []
-        for s in range(2):
-            for p in range(len(phis)):
-                self.orbs.append(dict(phi=phis[p], chi=chis[p], grad=grads[p], k=ks[p], f=fs[p], s=s))
+        for s, (crs, cls, occs) in enumerate(sets):
+            for ik in range(self.nk):
+                kg = (self.kfrac[ik][None, :] + w.miller[ik]) @ self.B     # (npw,3)
+                E = np.exp(1j * self.r @ kg.T) / math.sqrt(self.nk * self.omega)  # (Nr,npw)
+                for b in range(crs[ik].shape[0]):
+                    self.orbs.append(dict(phi=E @ crs[ik][b], chi=E @ (crs[ik][b] if cls is None else cls[ik][b]),
+                                          grad=np.stack([E @ (1j * kg[:, a] * crs[ik][b]) for a in range(3)]),
+                                          k=ik, f=float(occs[ik][b]), s=s))
         self._mat = {}
 
     # ------------------------------------------------------------------ kernels

@@ -147,6 +147,17 @@ class Problem:
             cr, cl = biorthogonalize_coeffs(cr, cl)
         self.cr, self.cl = cr, cl
         self.occ = [torch.as_tensor(o, dtype=RD) for o in w.occ]
+        # spin channels (Sec. 2.1, Eq. SCF: one orbital set per spin; unpolarized input: the same set)
+        self.polarized = getattr(w, "right_dn", None) is not None
+        if self.polarized:
+            crd = [torch.as_tensor(c, dtype=CD) for c in w.right_dn]
+            cld = None if w.left_dn is None else [torch.as_tensor(c, dtype=CD) for c in w.left_dn]
+            if cld is not None and biorthogonalize:
+                crd, cld = biorthogonalize_coeffs(crd, cld)
+            occd = [torch.as_tensor(o, dtype=RD) for o in (w.occ_dn if w.occ_dn is not None else w.occ)]
+            self.spin_sets = [(cr, cl, self.occ), (crd, cld, occd)]
+        else:
+            self.spin_sets = [(cr, cl, self.occ)] * 2
         self.miller = [np.asarray(m, dtype=np.int64) for m in w.miller]
         self._build_orbitals()
         self._gb()
@@ -180,25 +191,25 @@ class Problem:
         box[:, m[:, 0] % N1, m[:, 1] % N2, m[:, 2] % N3] = c
         return self.IFT(box) / math.sqrt(self.omega)
 
-    def _build_orbitals(self):
+    def _channel(self, cr, cl, occ):
         phi, chi, D, kidx, f = [], [], [], [], []
         for ik in range(self.nk):
-            p = self._to_real(self.cr[ik], ik)
+            p = self._to_real(cr[ik], ik)
             phi.append(p)
-            chi.append(p if self.cl is None else self._to_real(self.cl[ik], ik))
-            D.append(self._to_real(self.cr[ik], ik, grad=True))
+            chi.append(p if cl is None else self._to_real(cl[ik], ik))
+            D.append(self._to_real(cr[ik], ik, grad=True))
             kidx += [ik] * p.shape[0]
-            f.append(self.occ[ik])
-        phi = torch.cat(phi)
-        chi = torch.cat(chi)
-        D = torch.cat(D)
+            f.append(occ[ik])
         f = torch.cat(f)
-        # spin-unpolarized: both channels hold the same orbitals
-        self.orb = []
-        for _s in range(2):
-            self.orb.append(dict(phi=phi, chi=chi, D=D, f=f, w=f / self.nk,
-                                 k=np.array(kidx, dtype=np.int64)))
-        self.P = phi.shape[0]
+        return dict(phi=torch.cat(phi), chi=torch.cat(chi), D=torch.cat(D), f=f, w=f / self.nk,
+                    k=np.array(kidx, dtype=np.int64))
+
+    def _build_orbitals(self):
+        # one orbital set per spin channel; unpolarized input: both channels hold the same orbitals
+        up = self._channel(*self.spin_sets[0])
+        self.orb = [up, self._channel(*self.spin_sets[1]) if self.polarized else up]
+        self.P = up["phi"].shape[0]
+        assert self.orb[1]["phi"].shape[0] == self.P, "the same number of bands per spin channel is assumed"
         self.n = [torch.sum(o["w"][:, None, None, None] * torch.conj(o["chi"]) * o["phi"], 0)
                   for o in self.orb]
         self.J = [torch.sum(o["w"][:, None, None, None, None] * torch.conj(o["chi"])[:, None] * o["D"], 0)
@@ -616,14 +627,15 @@ class Problem:
         o = self.orb[s]
         return self.omega * torch.mean(torch.conj(o["chi"]) * g, dim=(-3, -2, -1))
 
-    def kinetic(self):
-        """<chi_p| -nabla^2/2 |phi_p> from the coefficients (Sec. 2.6.2)."""
+    def kinetic(self, s=0):
+        """<chi_p| -nabla^2/2 |phi_p> from the coefficients of spin channel s (Sec. 2.6.2)."""
+        cr, clx, _ = self.spin_sets[s]
         out = []
         for ik in range(self.nk):
             kg = (self.kfrac[ik][None, :] + self.miller[ik]) @ self.B
             t = torch.as_tensor(0.5 * np.sum(kg * kg, 1), dtype=RD)
-            cl = self.cr[ik] if self.cl is None else self.cl[ik]
-            out.append(torch.sum(torch.conj(cl) * t[None, :] * self.cr[ik], 1))
+            cl = cr[ik] if clx is None else clx[ik]
+            out.append(torch.sum(torch.conj(cl) * t[None, :] * cr[ik], 1))
         return torch.cat(out)
 
     def energy(self, terms=ALL_TERMS, with_kinetic=True, per_term=False):
@@ -632,7 +644,7 @@ class Problem:
         for s in range(2):
             f = self.orb[s]["f"]
             if with_kinetic:
-                parts["T"] = parts.get("T", 0) + torch.sum(f * self.kinetic()).real / self.nk
+                parts["T"] = parts.get("T", 0) + torch.sum(f * self.kinetic(s)).real / self.nk
             for t in terms:
                 fac = 0.5 if t in TERMS2 else MULT[t] / 3.0
                 e = torch.sum(f * self.braket(s, self.term(t, s))).real * fac / self.nk

@@ -9,12 +9,16 @@ central finite differences in tests/test_oracle_grad.py.
 Convention: grad_c = dE/dRe(c) + i dE/dIm(c) = 2 dE/dc* (Wirtinger), for the
 coefficients shared by both spin channels (TC mode, chi = phi = c); dA and dC
 are the partial derivatives with A_par, A_anti, C_par, C_anti independent.
+
+Biorthogonal mode (energy_and_grad_bitc): the gradients with respect to the right and the left
+coefficients of the energy Re sum f <chi| T + h2/2 + h3/3 |phi> (reading R8), with the pair taken
+as given (biorthonormalised once beforehand, not differentiated through).
 """
 from __future__ import annotations
 
 import torch
 
-from .fftroute import Problem, ALL_TERMS, RD, CD
+from .fftroute import Problem, ALL_TERMS, RD, CD, biorthogonalize_coeffs
 
 
 def energy_and_grad(w, terms=ALL_TERMS, div_correction=True, with_kinetic=True):
@@ -32,3 +36,32 @@ def energy(w, coeff=None, A=None, C=None, terms=ALL_TERMS, div_correction=True, 
         pr = Problem(w, A=A, C=C, coeff=None if coeff is None else [torch.as_tensor(c, dtype=CD) for c in coeff],
                      div_correction=div_correction)
         return float(pr.energy(terms=terms, with_kinetic=with_kinetic))
+
+
+def bitc_pair(w):
+    """The workload's right/left pair after the biorthonormalisation of Sec. 2.3 (numpy arrays)."""
+    cr, cl = biorthogonalize_coeffs([torch.as_tensor(c, dtype=CD) for c in w.right],
+                                    [torch.as_tensor(c, dtype=CD) for c in w.left])
+    return [c.numpy() for c in cr], [c.numpy() for c in cl]
+
+
+def energy_and_grad_bitc(w, right, left, terms=ALL_TERMS, div_correction=True):
+    """(E, grad_right, grad_left, dA, dC) of the biorthogonal-mode energy at the given pair."""
+    r = [torch.as_tensor(c, dtype=CD).clone().requires_grad_(True) for c in right]
+    l = [torch.as_tensor(c, dtype=CD).clone().requires_grad_(True) for c in left]
+    A = torch.as_tensor(w.A, dtype=RD).clone().requires_grad_(True)
+    C = torch.as_tensor(w.C, dtype=RD).clone().requires_grad_(True)
+    pr = Problem(w, A=A, C=C, coeff=r, left=l, div_correction=div_correction, biorthogonalize=False)
+    E = pr.energy(terms=terms)
+    g = torch.autograd.grad(E, r + l + [A, C])
+    nk = len(r)
+    return (float(E.detach()), [x.numpy() for x in g[:nk]], [x.numpy() for x in g[nk:2 * nk]],
+            g[-2].numpy(), g[-1].numpy())
+
+
+def energy_bitc(w, right, left, terms=ALL_TERMS, div_correction=True):
+    with torch.no_grad():
+        pr = Problem(w, coeff=[torch.as_tensor(c, dtype=CD) for c in right],
+                     left=[torch.as_tensor(c, dtype=CD) for c in left], div_correction=div_correction,
+                     biorthogonalize=False)
+        return float(pr.energy(terms=terms))

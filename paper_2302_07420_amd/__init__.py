@@ -71,6 +71,7 @@ def lib():
         "tc_orbital_energies": (I, [P, dp]),
         "tc_apply": (I, [P, I, dp, dp]),
         "tc_scf": (I, [P, ctypes.POINTER(SCFParams), dp, ctypes.POINTER(I)]),
+        "tc_energy_backward_lr": (I, [P, dp, dp, dp, dp]),
         "tc_get_orbitals": (I, [P, I, dp, dp]),
         "tc_apply_dev": (I, [P, I, P, P]),
         "tc_load_orbitals_dev": (I, [P, I, I, P, dp]),
@@ -250,6 +251,22 @@ class TCOperator:
                                                _dp(dA) if want_params else None, _dp(dC) if want_params else None),
                     "tc_energy_backward")
         return ([g[k, :, : self.npw[k]] for k in range(nk)] if want_grad else None), dA, dC
+
+    def backward_lr(self, want_right=True, want_left=True, want_params=True):
+        """(grad_right, grad_left, dA, dC); biorthogonal mode: the two partial gradients (TC mode: the
+        gradient as grad_right and want_left must be False)."""
+        nk = len(self.npw)
+        gr = np.zeros((nk, self.nband, self.npw_max), dtype=np.complex128) if want_right else None
+        gl = np.zeros_like(gr if gr is not None else np.zeros((nk, self.nband, self.npw_max), complex)) \
+            if want_left else None
+        dA = np.zeros(2) if want_params else None
+        dC = np.zeros(2) if want_params else None
+        self._check(self._L.tc_energy_backward_lr(self._h, None if gr is None else _dp(gr.view(np.float64)),
+                                                  None if gl is None else _dp(gl.view(np.float64)),
+                                                  None if dA is None else _dp(dA), None if dC is None else _dp(dC)),
+                    "tc_energy_backward_lr")
+        cut = lambda g: None if g is None else [g[k, :, : self.npw[k]].copy() for k in range(nk)]
+        return cut(gr), cut(gl), dA, dC
 
     def backward_dev(self, grad_ptr: Optional[int], want_params=True):
         """Gradient into a device buffer [nk][nband][npw_max] complex128; returns (dE/dA, dE/dC) or (None, None)."""

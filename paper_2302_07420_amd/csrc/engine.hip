@@ -154,6 +154,7 @@ struct Problem {
   std::vector<char> loaded;               // per k
   std::vector<char> left;                 // per k: loaded with left orbitals
   bool bitc = false;                      // every k-point has left orbitals (set by prepare)
+  bool negate_b = false;                  // grad-u . grad terms with sign -1 (the adjoint operator)
   double delta_gb = 0, sigma_aux = 0;
   int batch = 0;                          // targets per batch (0 = automatic)
 
@@ -302,10 +303,11 @@ __global__ void k_kinetic(const double* cl, const double* c, const double* kg, c
   if (threadIdx.x == 0) t[p] = red[0];
 }
 
-// Orbital gradient from an application with the GRADIENT tables and the grad-u . grad terms off:
-// grad_p = 4 w_p [(h' c_p)(G) + |k+G|^2/2 c_p(G)], w_p = f_p / N_k (both spin channels share c).
+// Orbital gradient from an application: grad_p = scale w_p [(h' c_p)(G) + |k+G|^2/2 c_p(G)], w_p = f_p / N_k.
+// TC mode: scale 4 (both spin channels share c, and bra and ket), h' with the GRADIENT tables and the
+// grad-u . grad terms off.  Biorthogonal mode: scale 2 for each of the right and left gradients.
 __global__ void k_grad_finish(const double* c, const double* out, const double* kg, const int* npw, const double* w,
-                              int nb, int npw_max, int P, double* grad) {
+                              int nb, int npw_max, int P, double scale, double* grad) {
   const long id = long(blockIdx.x) * blockDim.x + threadIdx.x;
   if (id >= long(P) * npw_max) return;
   const int p = int(id / npw_max), g = int(id - long(p) * npw_max), k = p / nb;
@@ -316,7 +318,7 @@ __global__ void k_grad_finish(const double* c, const double* out, const double* 
   }
   const double* q = kg + (long(k) * npw_max + g) * 3;
   const double e = 0.5 * (q[0] * q[0] + q[1] * q[1] + q[2] * q[2]);
-  const double f = 4.0 * w[p];
+  const double f = scale * w[p];
   o[0] = f * (out[2 * id] + e * c[2 * id]);
   o[1] = f * (out[2 * id + 1] + e * c[2 * id + 1]);
 }
@@ -1021,7 +1023,13 @@ struct EngineT : Engine {
   void apply(hipStream_t s, Shared& sh, const Problem& pb, double* stage_ms, const TargetSet* ts) override {
     const int P = pb.P();
     const int nb = pb.nb;
-    const Masks m = make_masks(pb.mask);
+    Masks m = make_masks(pb.mask);
+    if (pb.negate_b) {   // v2 -> v2^dagger: the grad-u . grad terms change sign (with the GRADIENT tables)
+      m.m2bh1 = -m.m2bh1;
+      m.m2bh2 = -m.m2bh2;
+      m.m2bx1 = -m.m2bx1;
+      m.m2bx2 = -m.m2bx2;
+    }
     ensure(pb, size_t(8) << 30);
     // targets: the orbitals, or nbt trial vectors per k-point
     const int nbt = ts ? ts->nvec : nb;
@@ -1656,7 +1664,8 @@ constexpr uint64_t kTerms3 = TC_T_3A1 | TC_T_3A2 | TC_T_3A3 | TC_T_3A4 | TC_T_3B
 //    by one application with V2a replaced by V2a - L~ and the grad-u . grad terms off.
 //  * A and C: central differences along exact tangent tables (TableVariant::TANGENT), exact because
 //    the energy is quadratic in the tables and correction prefactors taken together.
-int do_backward(tc_ctx* c, void* grad_dev, double* grad_host, double* dA, double* dC) {
+int do_backward(tc_ctx* c, void* grad_dev, double* grad_host, double* dA, double* dC, void* gl_dev = nullptr,
+                double* gl_host = nullptr) {
   Problem& pb = c->pb;
   const uint64_t m = pb.mask;
   if ((m & kTermsB) != 0 && (m & kTermsB) != kTermsB)
@@ -1667,14 +1676,20 @@ int do_backward(tc_ctx* c, void* grad_dev, double* grad_host, double* dA, double
     return fail(c, TC_ERR_UNSUPPORTED, "the gradient of the grad-u . grad terms needs 2ah and 2ax selected");
   int st = prepare(c);
   if (st != TC_OK) return st;
-  if (pb.bitc) return fail(c, TC_ERR_UNSUPPORTED, "the gradient is built for TC mode (no left orbitals)");
+  if (!pb.bitc && (gl_dev || gl_host)) return fail(c, TC_ERR_ARG, "no left orbitals loaded: grad_left must be NULL");
   struct Keep {
     tc_ctx* c;
     uint64_t mask;
     double e, parts[TC_E_NPARTS], stage[6], total;
     bool had;
     std::vector<double> eps;
+    bool swapped = false;
     ~Keep() {
+      if (swapped) {
+        std::swap(c->sh.coef.p, c->sh.coefL.p);
+        std::swap(c->sh.coef.n, c->sh.coefL.n);
+      }
+      c->pb.negate_b = false;
       c->pb.mask = mask;
       c->tables_dirty = true;   // the next application rebuilds the operator's tables
       c->e_total = e;
@@ -1689,19 +1704,51 @@ int do_backward(tc_ctx* c, void* grad_dev, double* grad_host, double* dA, double
   std::memcpy(keep.stage, c->stage_ms, sizeof(keep.stage));
   Shared& sh = c->sh;
   const int P = pb.P();
-  if (grad_dev || grad_host) {
-    pb.mask = m & ~kTermsB;
-    c->tables_dirty = true;
-    c->eng->upload_tables(pb, TableVariant{TableVariant::GRADIENT, 0, 0.0});
-    run_apply(c, nullptr, nullptr);
+  const size_t bytes = size_t(2) * P * pb.npw_max * sizeof(double);
+  auto finish = [&](double scale, void* ddev, double* dhost) {
     sh.grad.alloc(size_t(2) * P * pb.npw_max);
     hipLaunchKernelGGL(k_grad_finish, dim3(nblk(long(P) * pb.npw_max)), dim3(256), 0, c->stream, sh.coef.p, sh.out.p,
-                       sh.kg.p, sh.npw.p, sh.w.p, pb.nb, pb.npw_max, P, sh.grad.p);
-    const size_t bytes = size_t(2) * P * pb.npw_max * sizeof(double);
-    if (grad_dev) TC_HIP(hipMemcpyAsync(grad_dev, sh.grad.p, bytes, hipMemcpyDeviceToDevice, c->stream));
-    if (grad_host) TC_HIP(hipMemcpyAsync(grad_host, sh.grad.p, bytes, hipMemcpyDeviceToHost, c->stream));
+                       sh.kg.p, sh.npw.p, sh.w.p, pb.nb, pb.npw_max, P, scale, sh.grad.p);
+    if (ddev) TC_HIP(hipMemcpyAsync(ddev, sh.grad.p, bytes, hipMemcpyDeviceToDevice, c->stream));
+    if (dhost) TC_HIP(hipMemcpyAsync(dhost, sh.grad.p, bytes, hipMemcpyDeviceToHost, c->stream));
     TC_HIP(hipStreamSynchronize(c->stream));
-    pb.mask = m;
+  };
+  if (!pb.bitc) {
+    if (grad_dev || grad_host) {
+      pb.mask = m & ~kTermsB;
+      c->tables_dirty = true;
+      c->eng->upload_tables(pb, TableVariant{TableVariant::GRADIENT, 0, 0.0});
+      run_apply(c, nullptr, nullptr);
+      finish(4.0, grad_dev, grad_host);
+      pb.mask = m;
+    }
+  } else {
+    // E = Re sum f <chi| T + h2/2 + h3/3 |phi> with the pair held fixed:
+    //   2 dE/dchi* = 2 w (T + h) phi                    (Eq. BITCSCF: the operator itself)
+    //   2 dE/dphi* = 2 w (T + h^dagger) chi             (Eq. BITCSCFconj: the left operator)
+    // h^dagger is the operator with chi and phi exchanged and v2 replaced by its adjoint: the
+    // grad-u . grad terms change sign and the scalar kernel becomes V2a - L~ (the discrete adjoint of
+    // those terms is minus themselves minus the pair operator with kernel L~, as in the TC gradient).
+    if (gl_dev || gl_host) {
+      c->tables_dirty = true;
+      c->eng->upload_tables(pb, TableVariant{});
+      run_apply(c, nullptr, nullptr);
+      finish(2.0, gl_dev, gl_host);
+    }
+    if (grad_dev || grad_host) {
+      std::swap(sh.coef.p, sh.coefL.p);
+      std::swap(sh.coef.n, sh.coefL.n);
+      keep.swapped = true;
+      pb.negate_b = true;
+      c->tables_dirty = true;
+      c->eng->upload_tables(pb, TableVariant{TableVariant::GRADIENT, 0, 0.0});
+      run_apply(c, nullptr, nullptr);
+      finish(2.0, grad_dev, grad_host);
+      std::swap(sh.coef.p, sh.coefL.p);
+      std::swap(sh.coef.n, sh.coefL.n);
+      keep.swapped = false;
+      pb.negate_b = false;
+    }
   }
   for (int dir = 0; dir < 4; ++dir) {
     double* dst = dir < 2 ? (dA ? dA + dir : nullptr) : (dC ? dC + dir - 2 : nullptr);
@@ -2263,13 +2310,28 @@ int tc_energy(tc_ctx* c, double* e_total, double* e_parts) {
 int tc_energy_backward(tc_ctx* c, double* grad, double dA[2], double dC[2]) {
   return guard(c, [&]() -> int {
     if (!grad && !dA && !dC) return fail(c, TC_ERR_ARG, "nothing requested");
+    int st = prepare(c);
+    if (st != TC_OK) return st;
+    if (c->pb.bitc && grad)
+      return fail(c, TC_ERR_UNSUPPORTED, "left orbitals loaded: use tc_energy_backward_lr for the two gradients");
     return do_backward(c, nullptr, grad, dA, dC);
+  });
+}
+
+int tc_energy_backward_lr(tc_ctx* c, double* grad_right, double* grad_left, double dA[2], double dC[2]) {
+  return guard(c, [&]() -> int {
+    if (!grad_right && !grad_left && !dA && !dC) return fail(c, TC_ERR_ARG, "nothing requested");
+    return do_backward(c, nullptr, grad_right, dA, dC, nullptr, grad_left);
   });
 }
 
 int tc_energy_backward_dev(tc_ctx* c, void* grad_dev, double dA[2], double dC[2]) {
   return guard(c, [&]() -> int {
     if (!grad_dev && !dA && !dC) return fail(c, TC_ERR_ARG, "nothing requested");
+    int st = prepare(c);
+    if (st != TC_OK) return st;
+    if (c->pb.bitc && grad_dev)
+      return fail(c, TC_ERR_UNSUPPORTED, "left orbitals loaded: use tc_energy_backward_lr for the two gradients");
     return do_backward(c, grad_dev, nullptr, dA, dC);
   });
 }

@@ -1367,7 +1367,7 @@ __global__ void k_sum_parts(int mode, int S, int T, int t0, int slot, const R* h
 
 // Local (Hartree-type) terms added to the FP64 accumulators, then g_t = sum of the slots that belong to
 // the operator.  loc: [VH, h1 x3, P2bh2, F3b1, h6, F3b2]; D is stored component-major D[(c*P + p)*N^3 + r].
-// acc slots (kAccSlots): 0 = 2ah + 2ax, 1 = 2bx1 (kept out of g unless 2bx1 is selected), 2 = three-body
+// acc slots (kAccSlots): 0 = 2ah + 2ax, 1 = 2bx1 (unit weight; enters g times the 2bx1 multiplier), 2 = three-body
 // terms outside pass B, 3 = pass B (2bx2, 3b3, 3b4, 3b5), 4 = 2bh1, 5 = 2bh2.
 constexpr int kAccSlots = 6;
 
@@ -1403,10 +1403,9 @@ __global__ void k_local(const cx<R>* psi, const cx<R>* D, const cx<R>* loc, cons
     cx<double>& a = acc[s * TS + long(t) * NR + r];
     a.x += double(v[s].x);
     a.y += double(v[s].y);
-    if (s != 1 || m.m2bx1 != 0) {
-      gx += a.x;
-      gy += a.y;
-    }
+    const double ws = s == 1 ? m.m2bx1 : 1.0;   // slot 1 holds 2bx1 with unit weight
+    gx += ws * a.x;
+    gy += ws * a.y;
   }
   g[long(t) * NR + r] = mk<R>(R(gx), R(gy));
 }

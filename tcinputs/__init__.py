@@ -93,6 +93,10 @@ class Workload:
     C: tuple                       # (C_par, C_anti)
     alpha: float                   # Gygi-Baldereschi auxiliary exponent
     nelec_cell: int
+    # spin-polarised input: the down-spin channel's own orbitals and fillings (None: same as up)
+    right_dn: Optional[List[np.ndarray]] = None
+    left_dn: Optional[List[np.ndarray]] = None
+    occ_dn: Optional[List[np.ndarray]] = None
 
     @property
     def omega(self) -> float:
@@ -172,6 +176,27 @@ def perturbed_start(w, amp, seed, left_amp=None):
             z2 = rng.standard_normal(c.shape) + 1j * rng.standard_normal(c.shape)
             left.append(right[-1] + left_amp * z2 / np.sqrt(c.shape[1]))
     return w.replace(right=right, left=left if left_amp is not None else None)
+
+
+def polarized(w, seed, mix=0.3, occ_dn=None):
+    """A spin-polarised variant: the down channel's orbitals are the up ones rotated by a random unitary
+    mixing with other random smooth vectors of the same plane-wave sets (orthonormal), with fillings
+    occ_dn (default: the up fillings); a left set for the down channel when the workload has one."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    rd, ld = [], []
+    for ik, c in enumerate(w.right):
+        z = rng.standard_normal(c.shape) + 1j * rng.standard_normal(c.shape)
+        env = np.abs(c).max(axis=0) + 1e-3
+        q, r = np.linalg.qr((c + mix * z * env[None, :] / np.linalg.norm(env)).T)
+        q = q * (np.diag(r) / np.abs(np.diag(r)))[None, :]
+        rd.append(np.ascontiguousarray(q.T))
+        if w.left is not None:
+            z2 = rng.standard_normal(c.shape) + 1j * rng.standard_normal(c.shape)
+            ld.append(rd[-1] + 0.1 * z2 / np.sqrt(c.shape[1]))
+    od = [np.asarray(o, dtype=np.float64).copy() for o in w.occ] if occ_dn is None else \
+        [np.asarray(occ_dn, dtype=np.float64) for _ in w.occ]
+    return w.replace(right_dn=rd, left_dn=ld if w.left is not None else None, occ_dn=od,
+                     name=w.name + "_pol")
 
 
 def grid_fits(miller_list, grid) -> bool:

@@ -211,3 +211,31 @@ def test_orbital_energies_and_single_term_energies_fp64(case):
         Eg, _ = op.energy()
         op.close()
         assert abs(Eg - Et) < FP64_TOL * abs(Et), (t, Eg, Et)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_biorthogonal_gradients_vs_oracle(case, prec):
+    """2 dE/dchi* and 2 dE/dphi* (and dA, dC) against reverse-mode differentiation of the oracle."""
+    from oracle import grad as OG
+    name, w, per, tot, E = case
+    r, l = OG.bitc_pair(w)
+    Eo, gr0, gl0, dA0, dC0 = OG.energy_and_grad_bitc(w, r, l)
+    _say(f"[gpu] bitc {name} {prec}: right/left gradients vs oracle autograd")
+    op = tc.from_workload(w, precision=tc.TC_PREC_FP64 if prec == "fp64" else tc.TC_PREC_FP32)
+    E1, _ = op.energy()
+    gr, gl, dA, dC = op.backward_lr()
+    E2, _ = op.energy()
+    with pytest.raises(tc.TCError, match="status -5"):
+        op.backward()
+    op.close()
+    tol = 1e-10 if prec == "fp64" else 2e-6
+    sr = max(np.abs(x).max() for x in gr0)
+    sl = max(np.abs(x).max() for x in gl0)
+    er = max(np.abs(a - b).max() for a, b in zip(gr, gr0)) / sr
+    el = max(np.abs(a - b).max() for a, b in zip(gl, gl0)) / sl
+    ps = max(np.abs(dA0).max(), np.abs(dC0).max())
+    ep = max(np.abs(dA - dA0).max(), np.abs(dC - dC0).max()) / ps
+    _say(f"    right {er:.3e} left {el:.3e} params {ep:.3e}; E {E1!r} vs oracle {Eo!r}")
+    assert E2 == E1
+    assert er < tol and el < tol
+    assert ep < (1e-10 if prec == "fp64" else 1e-6)

@@ -44,3 +44,38 @@ def test_jastrow_parameter_gradient(case, which):
         Cm[i] -= h
         fd = (OG.energy(w, A=A, C=Cp) - OG.energy(w, A=A, C=Cm)) / (2 * h)
         assert gC[i] == pytest.approx(fd, rel=1e-6, abs=1e-9)
+
+
+# ---------------------------------------------------------------- biorthogonal mode
+@pytest.fixture(scope="module")
+def bitc_case():
+    w = T.tiny_fcc(kmesh=(2, 1, 1), grid=8, ecut=2.0, nb=2, a=6.0, occ=[1.0, 0.6], left_mix=0.2)
+    r, l = OG.bitc_pair(w)
+    return w, r, l, OG.energy_and_grad_bitc(w, r, l)
+
+
+@pytest.mark.parametrize("side", ["right", "left"])
+def test_bitc_gradients_match_central_differences(bitc_case, side):
+    w, r, l, (E, gr, gl, dA, dC) = bitc_case
+    rng = np.random.default_rng(5 if side == "right" else 6)
+    g = gr if side == "right" else gl
+    d = [0.3 * (rng.standard_normal(c.shape) + 1j * rng.standard_normal(c.shape)) for c in r]
+    h = 1e-5
+    e = []
+    for sgn in (1, -1):
+        rr = [a + sgn * h * b for a, b in zip(r, d)] if side == "right" else r
+        ll = [a + sgn * h * b for a, b in zip(l, d)] if side == "left" else l
+        e.append(OG.energy_bitc(w, rr, ll))
+    fd = (e[0] - e[1]) / (2 * h)
+    an = sum(np.sum((np.conj(gk) * dk).real) for gk, dk in zip(g, d))
+    assert an == pytest.approx(fd, rel=1e-7, abs=1e-10)
+
+
+def test_bitc_gradient_reduces_to_tc_when_left_equals_right():
+    """E_TC(c) = E_BITC(c, c): the two partial gradients add up to the TC gradient."""
+    w = T.tiny_fcc(kmesh=(2, 1, 1), grid=8, ecut=2.0, nb=2, a=6.0, occ=[1.0, 0.6])
+    E0, g0, _, _ = OG.energy_and_grad(w)
+    E, gr, gl, _, _ = OG.energy_and_grad_bitc(w, w.right, w.right)
+    assert E == pytest.approx(E0, rel=1e-13)
+    for a, b, c in zip(gr, gl, g0):
+        np.testing.assert_allclose(a + b, c, atol=1e-12 * np.abs(c).max())
