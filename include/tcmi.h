@@ -248,7 +248,7 @@ int tc_energy_backward_dev(tc_ctx* ctx, void* grad_dev, double dA[2], double dC[
  *      grad_left  = 2 dE/dchi* = 2 w (T + h) phi        (the operator of Eq. BITCSCF),
  *      grad_right = 2 dE/dphi* = 2 w (T + h^dagger) chi (the left operator of Eq. BITCSCFconj:
  *        chi and phi exchanged and v2 replaced by its adjoint, whose grad-u . grad terms change
- *        sign and whose scalar kernel becomes 4 pi/Q^2 - (grad u)^2~),
+ *        sign and whose scalar kernel becomes 4 pi/Q^2 - lap u~ - (grad u)^2~),
  *    w = f / N_k, one application each.
  * Term-mask conditions and errors as tc_energy_backward. */
 int tc_energy_backward_lr(tc_ctx* ctx, double* grad_right, double* grad_left, double dA[2], double dC[2]);

@@ -102,12 +102,18 @@ inline Jk jastrow_ft(double Q2, double A, double C) { return jastrow_ft_t<double
 //   GRADIENT: the scalar kernel V2a - L~ (L~ = -Q^2 u~, zero at Q = 0), i.e. 4 pi/Q^2 - (grad u)^2~ off
 //             Q = 0 and V2a(0) at Q = 0.  With the grad-u . grad terms switched off, one application with
 //             these tables gives the orbital gradient of the energy (see tc_energy_backward).
+//   ADJOINT:  the scalar kernel V2a - 2 L~, i.e. 4 pi/Q^2 - L - (grad u)^2~ off Q = 0 and V2a(0) at Q = 0.
+//             The discrete adjoint of the grad-u . grad terms is minus themselves minus twice the pair
+//             operator with kernel L~, so the adjoint operator h^dagger is one application with these
+//             tables, the grad-u . grad terms at multiplier -1 and left and right orbitals exchanged.
 //   TANGENT:   every quantity that depends on (A, C) moved along its exact derivative with respect to one
 //             parameter: K + h dK/dtheta (theta = A_par, A_anti, C_par, C_anti).  The energy is a
 //             polynomial of degree two in these quantities taken together, so a central difference over
 //             +-h along the tangent is its exact derivative.
 struct TableVariant {
-  enum Kind { OPERATOR = 0, GRADIENT = 1, TANGENT = 2 } kind = OPERATOR;
+  enum Kind { OPERATOR = 0, GRADIENT = 1, TANGENT = 2, ADJOINT = 3 } kind = OPERATOR;
+  // multiplier of L = lap u~ in the scalar kernels away from Q = 0
+  double lap_factor() const { return kind == GRADIENT ? 0.0 : kind == ADJOINT ? -1.0 : 1.0; }
   int dir = 0;
   double h = 0;
 };
@@ -810,10 +816,10 @@ struct EngineT : Engine {
   }
 
   // Exchange-type tables at Q = Delta + G: V2a parallel (Q = 0: 1/r dropped, L(0) - W(0)), u~ (Q = 0: 0).
-  // GRADIENT variant: V2a - L~ (Q != 0: 4 pi/Q^2 - W; Q = 0 unchanged).
+  // GRADIENT variant: V2a - L~ (Q != 0: 4 pi/Q^2 - W), ADJOINT: V2a - 2 L~; Q = 0 unchanged.
   static void fill_delta(const Problem& pb, const TableVariant& tv, const double* f, double scale, R* V, R* U1,
                          R* U2) {
-    const bool grad = tv.kind == TableVariant::GRADIENT;
+    const double lf = tv.lap_factor();
     const double V0 = scale * chan_eval(tv, pb.A, pb.C, 0, [](auto A, auto C) {
                         return -kFourPi * A - 2.0 * kPi * A * A / C;
                       });
@@ -830,7 +836,7 @@ struct EngineT : Engine {
       }
       const Jk k0 = chan_kernels(tv, pb.A, pb.C, 0, q2);
       const Jk k1 = chan_kernels(tv, pb.A, pb.C, 1, q2);
-      V[r] = R(scale * (kFourPi / q2 + (grad ? 0.0 : k0.lap) - k0.w));
+      V[r] = R(scale * (kFourPi / q2 + lf * k0.lap - k0.w));
       U1[r] = R(scale * k0.u);
       U2[r] = R(scale * k1.u);
     }
@@ -869,7 +875,7 @@ struct EngineT : Engine {
     TC_HIP(hipMemcpy(tU2.p, U2.data(), U2.size() * sizeof(R), hipMemcpyHostToDevice));
     TC_HIP(hipMemcpy(dfr.p, df.data(), df.size() * sizeof(double), hipMemcpyHostToDevice));
     // Hartree tables (Delta = 0, G = 0 dropped); both spin channels summed for the working precision
-    const bool grad = tv.kind == TableVariant::GRADIENT;
+    const double lf = tv.lap_factor();
     std::vector<R> HV(NR), HU(NR);
     std::vector<double> hu0(NR), hu1(NR);
     for (long r = 0; r < NR; ++r) {
@@ -882,7 +888,7 @@ struct EngineT : Engine {
       const Jk k0 = chan_kernels(tv, pb.A, pb.C, 0, q2);
       const Jk k1 = chan_kernels(tv, pb.A, pb.C, 1, q2);
       const double v = kFourPi / q2;
-      const double l0 = grad ? 0.0 : k0.lap, l1 = grad ? 0.0 : k1.lap;
+      const double l0 = lf * k0.lap, l1 = lf * k1.lap;
       HV[r] = R(scale * ((v + l0 - k0.w) + (v + l1 - k1.w)));
       HU[r] = R(scale * (k0.u + k1.u));
       hu0[r] = scale * k0.u;
@@ -1024,7 +1030,7 @@ struct EngineT : Engine {
     const int P = pb.P();
     const int nb = pb.nb;
     Masks m = make_masks(pb.mask);
-    if (pb.negate_b) {   // v2 -> v2^dagger: the grad-u . grad terms change sign (with the GRADIENT tables)
+    if (pb.negate_b) {   // v2 -> v2^dagger: the grad-u . grad terms change sign (with the ADJOINT tables)
       m.m2bh1 = -m.m2bh1;
       m.m2bh2 = -m.m2bh2;
       m.m2bx1 = -m.m2bx1;
@@ -1727,8 +1733,9 @@ int do_backward(tc_ctx* c, void* grad_dev, double* grad_host, double* dA, double
     //   2 dE/dchi* = 2 w (T + h) phi                    (Eq. BITCSCF: the operator itself)
     //   2 dE/dphi* = 2 w (T + h^dagger) chi             (Eq. BITCSCFconj: the left operator)
     // h^dagger is the operator with chi and phi exchanged and v2 replaced by its adjoint: the
-    // grad-u . grad terms change sign and the scalar kernel becomes V2a - L~ (the discrete adjoint of
-    // those terms is minus themselves minus the pair operator with kernel L~, as in the TC gradient).
+    // grad-u . grad terms change sign and the scalar kernel becomes V2a - 2 L~ (the discrete adjoint of
+    // those terms is minus themselves minus twice the pair operator with kernel L~; their sum with the
+    // operator gives the V2a - L~ of the TC gradient).
     if (gl_dev || gl_host) {
       c->tables_dirty = true;
       c->eng->upload_tables(pb, TableVariant{});
@@ -1741,7 +1748,7 @@ int do_backward(tc_ctx* c, void* grad_dev, double* grad_host, double* dA, double
       keep.swapped = true;
       pb.negate_b = true;
       c->tables_dirty = true;
-      c->eng->upload_tables(pb, TableVariant{TableVariant::GRADIENT, 0, 0.0});
+      c->eng->upload_tables(pb, TableVariant{TableVariant::ADJOINT, 0, 0.0});
       run_apply(c, nullptr, nullptr);
       finish(2.0, grad_dev, grad_host);
       std::swap(sh.coef.p, sh.coefL.p);
