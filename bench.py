@@ -32,7 +32,7 @@ HBM_PEAK_GBS = 8000.0
 # averaged over the launches of the step.  Keyed by kernel and by the hash of the library sources the
 # counters were taken on: any later change to those sources makes the figure stale (reported as null).
 MEASURED_TRAFFIC = {
-    ("k_fused_A<float,24>", "91cdf69f8d220fb3"): 9.0532e9,
+    ("k_fused_A<float,24>", "6958dd058c0e15ee"): 9.0355e9,
 }
 
 
