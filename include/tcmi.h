@@ -144,11 +144,31 @@ int tc_load_orbitals(tc_ctx* ctx, int ik, int nband, const double* right, const 
 /* Same, TC mode, from a device buffer (complex128, [nband][npw(ik)]); occ stays on the host. */
 int tc_load_orbitals_dev(tc_ctx* ctx, int ik, int nband, const void* right_dev, const double* occ);
 
+/* Number of spin channels (Sec. 2.1 and Eq. SCF: one orbital set per spin; Sec. 2.6 sums every
+ * Hartree-type field over both spins with the Jastrow channel u^{s s'} of the pair).  nspin = 1
+ * (default): both channels hold the orbitals of tc_load_orbitals.  nspin = 2: spin-polarised TC mode,
+ * the spin-down set is loaded with tc_load_orbitals_spin(ctx, 1, ...), the spin-up set with
+ * tc_load_orbitals or spin 0.  Both channels have the same nband; exchange-type terms pair orbitals of
+ * one spin, the parallel channel serves the own spin's density and partners and the antiparallel channel
+ * the other spin's.  Outputs become spin-major: tc_apply_all* writes [2][nk][nband][npw_max] and
+ * tc_orbital_energies [2][nk][nband] complex128; tc_energy sums both channels.  Call after the k-mesh;
+ * it discards every loaded orbital.  Built for tc_apply_all*, tc_energy and tc_orbital_energies;
+ * tc_apply*, tc_scf and tc_energy_backward* return TC_ERR_UNSUPPORTED with two channels.
+ * TC_ERR_ARG unless nspin is 1 or 2; TC_ERR_STATE before the k-mesh. */
+int tc_set_nspin(tc_ctx* ctx, int nspin);
+
+/* tc_load_orbitals for spin channel `spin` (0 = up, the set of tc_load_orbitals; 1 = down, needs
+ * tc_set_nspin(ctx, 2)).  TC mode only: left must be NULL (TC_ERR_UNSUPPORTED otherwise).  occ are the
+ * channel's own fillings in [0, 1].  TC_ERR_STATE for spin 1 with one channel; TC_ERR_ARG for another
+ * spin. */
+int tc_load_orbitals_spin(tc_ctx* ctx, int spin, int ik, int nband, const double* right, const double* left,
+                          const double* occ);
+
 /* Apply the selected two- and three-body terms (with corrections) to every
  * loaded orbital.  `out` (host) receives [nk][nband][npw_max] complex128
  * coefficients (H c)(G) = sqrt(Omega) FT[g](G) on each k-point's plane-wave set,
- * zero-padded to npw_max = max npw.  The energies of this application are kept
- * for tc_energy. */
+ * zero-padded to npw_max = max npw (with two spin channels, [2][nk][nband][npw_max],
+ * spin-major).  The energies of this application are kept for tc_energy. */
 int tc_apply_all(tc_ctx* ctx, double* out);
 
 /* Same, writing to a caller-owned device buffer of the same layout (may be NULL:
@@ -212,7 +232,8 @@ int tc_get_orbitals(tc_ctx* ctx, int ik, double* right, double* left);
 /* Orbital energies of the last application (runs one if needed): eps receives [nk][nband]
  * complex128, eps_j = <chi_j| T + h2 + h3 |phi_j> with the selected terms and corrections (the
  * diagonal elements of Eqs. SCF / BITCSCF, chi = phi in TC mode; Re eps_jj is the one-electron
- * energy of Sec. 2.3).  Per spin channel (both channels are equal). */
+ * energy of Sec. 2.3).  Per spin channel: one set with nspin = 1 (both channels are equal),
+ * [2][nk][nband] with two channels. */
 int tc_orbital_energies(tc_ctx* ctx, double* eps);
 
 /* Gradient of the pseudo-energy of the loaded orbitals (the functional returned by

@@ -68,6 +68,8 @@ def lib():
         "tc_set_jastrow": (I, [P, dp, dp]),
         "tc_set_options": (I, [P, I, D, I, ctypes.c_uint64]),
         "tc_load_orbitals": (I, [P, I, I, dp, dp, dp]),
+        "tc_set_nspin": (I, [P, I]),
+        "tc_load_orbitals_spin": (I, [P, I, I, I, dp, dp, dp]),
         "tc_orbital_energies": (I, [P, dp]),
         "tc_apply": (I, [P, I, dp, dp]),
         "tc_scf": (I, [P, ctypes.POINTER(SCFParams), dp, ctypes.POINTER(I)]),
@@ -110,6 +112,7 @@ class TCOperator:
         self._h = h
         self.npw: List[int] = []
         self.nband = 0
+        self.nspin = 1
 
     def _check(self, st: int, what: str):
         if st != 0:
@@ -154,9 +157,15 @@ class TCOperator:
         self._check(self._L.tc_set_options(self._h, int(precision), float(alpha), int(bool(div_correction)),
                                            int(terms)), "tc_set_options")
 
-    def load_orbitals(self, ik, coeff, occ, left=None):
+    def set_nspin(self, nspin: int):
+        """1: both spin channels hold the same orbitals; 2: spin-polarised TC mode (load spin 1 separately)."""
+        self._check(self._L.tc_set_nspin(self._h, int(nspin)), "tc_set_nspin")
+        self.nspin = int(nspin)
+
+    def load_orbitals(self, ik, coeff, occ, left=None, spin=0):
         """Right orbitals ``coeff`` (nband, npw) of k-point ik; ``left`` (same shape) switches that k-point to
-        the biorthogonal mode (the library normalises the right set and biorthogonalises the left one)."""
+        the biorthogonal mode (the library normalises the right set and biorthogonalises the left one).
+        ``spin`` = 1 loads the spin-down channel of a spin-polarised problem (after set_nspin(2))."""
         c = np.ascontiguousarray(np.asarray(coeff, dtype=np.complex128))
         o = np.ascontiguousarray(np.asarray(occ, dtype=np.float64))
         lp = None
@@ -166,6 +175,10 @@ class TCOperator:
                 raise ValueError("left and right coefficient arrays differ in shape")
             lp = _dp(lc.view(np.float64))
         self.nband = c.shape[0]
+        if spin:
+            self._check(self._L.tc_load_orbitals_spin(self._h, int(spin), ik, c.shape[0], _dp(c.view(np.float64)),
+                                                      lp, _dp(o)), "tc_load_orbitals_spin")
+            return
         self._check(self._L.tc_load_orbitals(self._h, ik, c.shape[0], _dp(c.view(np.float64)), lp, _dp(o)),
                     "tc_load_orbitals")
 
@@ -180,14 +193,16 @@ class TCOperator:
     def npw_max(self):
         return max(self.npw) if self.npw else 0
 
-    def apply(self) -> List[np.ndarray]:
+    def apply(self):
+        """(H c) per k-point as (nband, npw) arrays; with two spin channels, one such list per spin."""
         nk = len(self.npw)
         if nk == 0 or self.npw_max == 0 or self.nband == 0:
             # let the library report the missing set-up (TC_ERR_STATE)
             self._check(self._L.tc_apply_all(self._h, None), "tc_apply_all")
-        out = np.zeros((nk, self.nband, self.npw_max), dtype=np.complex128)
+        out = np.zeros((self.nspin, nk, self.nband, self.npw_max), dtype=np.complex128)
         self._check(self._L.tc_apply_all(self._h, _dp(out.view(np.float64))), "tc_apply_all")
-        return [out[k, :, : self.npw[k]] for k in range(nk)]
+        per = [[out[s, k, :, : self.npw[k]] for k in range(nk)] for s in range(self.nspin)]
+        return per[0] if self.nspin == 1 else per
 
     def apply_dev(self, out_ptr: Optional[int] = None):
         self._check(self._L.tc_apply_all_dev(self._h, ctypes.c_void_p(out_ptr) if out_ptr else None),
@@ -236,10 +251,12 @@ class TCOperator:
         return (r, l) if left else r
 
     def orbital_energies(self) -> np.ndarray:
-        """Complex eps_j = <chi_j| T + h |phi_j> per orbital of the last application, shape [nk, nband]."""
-        e = np.zeros(len(self.npw) * self.nband, dtype=np.complex128)
+        """Complex eps_j = <chi_j| T + h |phi_j> per orbital of the last application, shape [nk, nband]
+        ([2, nk, nband] with two spin channels)."""
+        e = np.zeros(self.nspin * len(self.npw) * self.nband, dtype=np.complex128)
         self._check(self._L.tc_orbital_energies(self._h, _dp(e.view(np.float64))), "tc_orbital_energies")
-        return e.reshape(len(self.npw), self.nband)
+        shape = (len(self.npw), self.nband) if self.nspin == 1 else (2, len(self.npw), self.nband)
+        return e.reshape(shape)
 
     def backward(self, want_grad=True, want_params=True):
         """(grad per k as (nband, npw) complex128 = 2 dE/dc*, dE/dA (2,), dE/dC (2,)); unrequested parts are None."""
@@ -315,8 +332,14 @@ def from_workload(w, precision=TC_PREC_FP64, terms=TERM_ALL, div_correction=True
     op.set_options(precision, w.alpha, div_correction, terms)
     cs = w.right if coeff is None else coeff
     ls = w.left if left is None else left
+    dn = getattr(w, "right_dn", None)
+    if dn is not None:   # spin-polarised workload (TC mode)
+        op.set_nspin(2)
     for ik in range(len(w.miller)):
         op.load_orbitals(ik, cs[ik], w.occ[ik], None if ls is None else ls[ik])
+        if dn is not None:
+            occd = w.occ_dn if w.occ_dn is not None else w.occ
+            op.load_orbitals(ik, dn[ik], occd[ik], spin=1)
     return op
 
 

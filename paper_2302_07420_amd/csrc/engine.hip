@@ -161,6 +161,9 @@ struct Problem {
   std::vector<char> left;                 // per k: loaded with left orbitals
   bool bitc = false;                      // every k-point has left orbitals (set by prepare)
   bool negate_b = false;                  // grad-u . grad terms with sign -1 (the adjoint operator)
+  int nspin = 1;                          // 2: spin-polarised, the down channel's own orbitals
+  std::vector<double> occ_dn;             // [nk][nb] fillings of the down channel (nspin = 2)
+  std::vector<char> loaded_dn;            // per k (nspin = 2)
   double delta_gb = 0, sigma_aux = 0;
   int batch = 0;                          // targets per batch (0 = automatic)
 
@@ -517,6 +520,16 @@ __global__ void k_corr_gfields(const double* u0, const double* u1, double c0, do
   out[r] = (c0 * u0[r] + c1 * u1[r]) * in[r];
 }
 
+// spin-polarised form: out = c0 u0 in_own + c1 u1 in_other
+template <int N>
+__global__ void k_corr_gfields2(const double* u0, const double* u1, double c0, double c1, const cx<double>* in,
+                                const cx<double>* ino, cx<double>* out) {
+  constexpr long NR = long(N) * N * N;
+  const long r = long(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (r >= NR) return;
+  out[r] = (c0 * u0[r]) * in[r] + (c1 * u1[r]) * ino[r];
+}
+
 // per-orbital products F * psi_p for two fields (batched output [2][P][NR])
 template <int N>
 __global__ void k_corr_products(const cx<double>* F, const cx<double>* psi, int P, cx<double>* out) {
@@ -790,12 +803,18 @@ struct EngineT : Engine {
   DBuf<cx<R>> Hbpart;       // [S][T][3][NR]
   DBuf<cx<double>> chi64;   // [P][NR]  FP64 left orbitals for the corrections
   bool bitc_alloc = false;
+  // spin-polarised runs: the down channel's fields, the antiparallel-channel h5 of each channel, scratch
+  DBuf<cx<R>> psi1, D1, Dl1, Hl1, H3a4_1, nJ1, loc1, wk2;
+  DBuf<R> h5_1, h5a0, h5a1;
+  DBuf<cx<double>> psi64_1, v64p;
+  int nspin_alloc = 1;
   // target set of tc_apply (trial vectors)
   DBuf<cx<R>> psiT, DT;              // [NT][NR], [3][NT][NR]
   DBuf<cx<double>> psiT64, prodT;    // [NT][NR], [2][NT][NR]
   int S = 1;
   // kernel tables (scaled by 1/(Omega N^3))
   DBuf<R> tV, tU1, tU2, tHV, tHU;
+  DBuf<R> tHVp, tHVa, tHUp, tHUa;   // Hartree tables per channel (spin-polarised runs)
   DBuf<double> dfr;
   // FP64 side of the corrections
   DBuf<cx<double>> psi64, v64, prod64;
@@ -876,12 +895,12 @@ struct EngineT : Engine {
     TC_HIP(hipMemcpy(dfr.p, df.data(), df.size() * sizeof(double), hipMemcpyHostToDevice));
     // Hartree tables (Delta = 0, G = 0 dropped); both spin channels summed for the working precision
     const double lf = tv.lap_factor();
-    std::vector<R> HV(NR), HU(NR);
+    std::vector<R> HV(NR), HU(NR), HVp(NR), HVa(NR), HUp(NR), HUa(NR);
     std::vector<double> hu0(NR), hu1(NR);
     for (long r = 0; r < NR; ++r) {
       double Q[3], q2;
       if (!grid_q(pb, r, nullptr, Q, q2) || q2 < 1e-20) {
-        HV[r] = HU[r] = R(0);
+        HV[r] = HU[r] = HVp[r] = HVa[r] = HUp[r] = HUa[r] = R(0);
         hu0[r] = hu1[r] = 0;
         continue;
       }
@@ -891,6 +910,10 @@ struct EngineT : Engine {
       const double l0 = lf * k0.lap, l1 = lf * k1.lap;
       HV[r] = R(scale * ((v + l0 - k0.w) + (v + l1 - k1.w)));
       HU[r] = R(scale * (k0.u + k1.u));
+      HVp[r] = R(scale * (v + l0 - k0.w));
+      HVa[r] = R(scale * (v + l1 - k1.w));
+      HUp[r] = R(scale * k0.u);
+      HUa[r] = R(scale * k1.u);
       hu0[r] = scale * k0.u;
       hu1[r] = scale * k1.u;
     }
@@ -899,6 +922,11 @@ struct EngineT : Engine {
     tHu0.alloc(NR);
     tHu1.alloc(NR);
     TC_HIP(hipMemcpy(tHV.p, HV.data(), NR * sizeof(R), hipMemcpyHostToDevice));
+    for (auto* b : {&tHVp, &tHVa, &tHUp, &tHUa}) b->alloc(NR);
+    TC_HIP(hipMemcpy(tHVp.p, HVp.data(), NR * sizeof(R), hipMemcpyHostToDevice));
+    TC_HIP(hipMemcpy(tHVa.p, HVa.data(), NR * sizeof(R), hipMemcpyHostToDevice));
+    TC_HIP(hipMemcpy(tHUp.p, HUp.data(), NR * sizeof(R), hipMemcpyHostToDevice));
+    TC_HIP(hipMemcpy(tHUa.p, HUa.data(), NR * sizeof(R), hipMemcpyHostToDevice));
     TC_HIP(hipMemcpy(tHU.p, HU.data(), NR * sizeof(R), hipMemcpyHostToDevice));
     TC_HIP(hipMemcpy(tHu0.p, hu0.data(), NR * sizeof(double), hipMemcpyHostToDevice));
     TC_HIP(hipMemcpy(tHu1.p, hu1.data(), NR * sizeof(double), hipMemcpyHostToDevice));
@@ -980,7 +1008,7 @@ struct EngineT : Engine {
 
   void ensure(const Problem& pb, size_t budget_bytes) {
     const int P = pb.P();
-    if (P == P_alloc && pb.batch == batch_alloc && pb.bitc == bitc_alloc) return;
+    if (P == P_alloc && pb.batch == batch_alloc && pb.bitc == bitc_alloc && pb.nspin == nspin_alloc) return;
     psi.alloc(size_t(P) * NR);
     D.alloc(size_t(3) * P * NR);
     Dl.alloc(size_t(3) * P * NR);
@@ -1021,12 +1049,33 @@ struct EngineT : Engine {
       Hbpart.alloc(size_t(S) * 3 * T * NR);
       chi64.alloc(size_t(P) * NR);
     }
+    if (pb.nspin == 2) {
+      psi1.alloc(size_t(P) * NR);
+      D1.alloc(size_t(3) * P * NR);
+      Dl1.alloc(size_t(3) * P * NR);
+      Hl1.alloc(size_t(3) * P * NR);
+      H3a4_1.alloc(size_t(3) * P * NR);
+      nJ1.alloc(4 * NR);
+      loc1.alloc(8 * NR);
+      wk2.alloc(16 * NR);
+      h5_1.alloc(size_t(P) * NR);
+      h5a0.alloc(size_t(P) * NR);
+      h5a1.alloc(size_t(P) * NR);
+      h5part.alloc(size_t(2) * S * T * NR);
+      psi64_1.alloc(size_t(P) * NR);
+      v64p.alloc(10 * NR);
+    }
     P_alloc = P;
     batch_alloc = pb.batch;
     bitc_alloc = pb.bitc;
+    nspin_alloc = pb.nspin;
   }
 
   void apply(hipStream_t s, Shared& sh, const Problem& pb, double* stage_ms, const TargetSet* ts) override {
+    if (pb.nspin == 2) {   // spin-polarised (TC mode, orbitals as targets)
+      apply_pol(s, sh, pb, stage_ms);
+      return;
+    }
     const int P = pb.P();
     const int nb = pb.nb;
     Masks m = make_masks(pb.mask);
@@ -1323,6 +1372,356 @@ struct EngineT : Engine {
     stage_ms[5] = ev.ms(3, 5) - msA - msB;
   }
 
+  // Spin-polarised application (TC mode): each spin channel has its own orbitals.  Exchange-type terms
+  // pair orbitals of one spin; the Hartree-type fields, 3a2 (h6), 3b1, 3b2 and the 3b6 chain take the
+  // parallel-channel kernels for the own spin and the antiparallel-channel ones for the other spin.
+  // Layout: channel sp's coefficients, outputs and energies follow those of channel 0 (spin-major).
+  void apply_pol(hipStream_t s, Shared& sh, const Problem& pb, double* stage_ms) {
+    const int P = pb.P();
+    const int nb = pb.nb;
+    const int npm = pb.npw_max;
+    const Masks m = make_masks(pb.mask);
+    ensure(pb, size_t(8) << 30);
+    const MeshInfo mi{pb.n1, pb.n2, pb.n3, nb, P, nb};
+    Recip rc;
+    for (int i = 0; i < 9; ++i) rc.b[i] = pb.B[i];
+    Basis<R> bm, mm;
+    for (int i = 0; i < 9; ++i) bm.b[i] = R(pb.B[i]);
+    for (int d = 0; d < 3; ++d)
+      for (int e = 0; e < 3; ++e)
+        mm.b[3 * d + e] = R(pb.B[3 * d] * pb.B[3 * e] + pb.B[3 * d + 1] * pb.B[3 * e + 1] + pb.B[3 * d + 2] * pb.B[3 * e + 2]);
+    const Tables tb{tV.p, tU1.p, tU2.p, dfr.p};
+    const double fb = double(sizeof(cx<R>)) * NR;
+    const double fd = double(sizeof(cx<double>)) * NR;
+    const double tabB = 3.0 * double(sizeof(R)) * NR * double((2 * pb.n1 - 1) * (2 * pb.n2 - 1) * (2 * pb.n3 - 1));
+    Prof* pf = prof;
+    auto K = [&](int id, double bytes, auto&& launch) {
+      ProfScope ps(pf, s, id, bytes);
+      launch();
+    };
+    cx<R>* PSI[2] = {psi.p, psi1.p};
+    cx<R>* DD[2] = {D.p, D1.p};
+    cx<R>* DL[2] = {Dl.p, Dl1.p};
+    cx<R>* HL[2] = {Hl.p, Hl1.p};
+    cx<R>* H3[2] = {H3a4.p, H3a4_1.p};
+    cx<R>* NJ[2] = {nJ.p, nJ1.p};
+    cx<R>* LOC[2] = {loc.p, loc1.p};
+    R* H5P[2] = {h5.p, h5_1.p};
+    R* H5A[2] = {h5a0.p, h5a1.p};
+    const double* W[2] = {sh.w.p, sh.w.p + P};
+    const size_t cofs = size_t(2) * P * npm;   // doubles per channel in coefficient arrays
+    Events ev(6);
+    double msA = 0, msB = 0;
+    TC_HIP(hipEventRecord(ev.e[0], s));
+
+    // ---- 0: G -> r for both channels
+    const unsigned gsc = nblk(long(P) * npm);
+    for (int sp = 0; sp < 2; ++sp) {
+      TC_HIP(hipMemsetAsync(PSI[sp], 0, size_t(P) * NR * sizeof(cx<R>), s));
+      TC_HIP(hipMemsetAsync(DD[sp], 0, size_t(3) * P * NR * sizeof(cx<R>), s));
+      const double* cf = sh.coef.p + sp * cofs;
+      K(TC_K_SCATTER, 0.0, [&] {
+        hipLaunchKernelGGL((k_scatter<R>), dim3(gsc), dim3(256), 0, s, cf, sh.boxidx.p, sh.npw.p, sh.kg.p, nb, npm, P,
+                           -1, PSI[sp], NR);
+        for (int c = 0; c < 3; ++c)
+          hipLaunchKernelGGL((k_scatter<R>), dim3(gsc), dim3(256), 0, s, cf, sh.boxidx.p, sh.npw.p, sh.kg.p, nb, npm,
+                             P, c, DD[sp] + size_t(c) * P * NR, NR);
+      });
+      fft3d_t<R, N>(PSI[sp], P, +1, s, pf);
+      fft3d_t<R, N>(DD[sp], 3L * P, +1, s, pf);
+      K(TC_K_OTHER, 6.0 * fb * P, [&] {
+        hipLaunchKernelGGL((k_lattice3<R, N>), dim3(nblk(long(P) * NR)), dim3(256), 0, s, DD[sp], DL[sp], bm, long(P),
+                           NR, long(P) * NR);
+      });
+    }
+    TC_HIP(hipEventRecord(ev.e[1], s));
+
+    // ---- 1: densities of both channels; Hartree-type fields of each target spin
+    // wk2: [0..3] n~, J~ of channel 0, [4..7] of channel 1, [8..10] / [11..13] products or M per channel
+    for (int sp = 0; sp < 2; ++sp) {
+      TC_HIP(hipMemsetAsync(LOC[sp], 0, 8 * NR * sizeof(cx<R>), s));
+      K(TC_K_OTHER, fb * (4.0 * P + 4.0), [&] {
+        hipLaunchKernelGGL((k_density<R, N>), dim3(nblk(NR)), dim3(256), 0, s, PSI[sp], PSI[sp], DD[sp], W[sp], P,
+                           NJ[sp], NJ[sp] + NR);
+      });
+      TC_HIP(hipMemcpyAsync(wk2.p + 4 * sp * NR, NJ[sp], 4 * NR * sizeof(cx<R>), hipMemcpyDeviceToDevice, s));
+    }
+    fft3d_t<R, N>(wk2.p, 8, -1, s, pf);
+    for (int sp = 0; sp < 2; ++sp) {
+      const int o = 1 - sp;
+      K(TC_K_OTHER, fb * 13.0, [&] {
+        hipLaunchKernelGGL((k_hartree_g2<R, N>), dim3(nblk(NR)), dim3(256), 0, s, rc, tHVp.p, tHVa.p, tHUp.p, tHUa.p,
+                           wk2.p + 4 * sp * NR, wk2.p + (4 * sp + 1) * NR, wk2.p + 4 * o * NR,
+                           wk2.p + (4 * o + 1) * NR, wk.p);
+      });
+      fft3d_t<R, N>(wk.p, 5, +1, s, pf);
+      TC_HIP(hipMemcpyAsync(LOC[sp], wk.p, 5 * NR * sizeof(cx<R>), hipMemcpyDeviceToDevice, s));
+    }
+    // 3b1: sum_s1 -i G . u^{s s1} FT(h1^{s1} n_{s1})
+    for (int sp = 0; sp < 2; ++sp)
+      K(TC_K_OTHER, fb * 7.0, [&] {
+        hipLaunchKernelGGL((k_mul_vec_scalar<R, N>), dim3(nblk(NR)), dim3(256), 0, s, LOC[sp] + NR, NJ[sp],
+                           wk2.p + (8 + 3 * sp) * NR);
+      });
+    fft3d_t<R, N>(wk2.p + 8 * NR, 6, -1, s, pf);
+    for (int sp = 0; sp < 2; ++sp) {
+      const int o = 1 - sp;
+      K(TC_K_OTHER, fb * 7.0, [&] {
+        hipLaunchKernelGGL((k_gdiv2<R, N>), dim3(nblk(NR)), dim3(256), 0, s, rc, tHUp.p, tHUa.p,
+                           wk2.p + (8 + 3 * sp) * NR, wk2.p + (8 + 3 * o) * NR, wk.p);
+      });
+      fft3d_t<R, N>(wk.p, 1, +1, s, pf);
+      TC_HIP(hipMemcpyAsync(LOC[sp] + 5 * NR, wk.p, NR * sizeof(cx<R>), hipMemcpyDeviceToDevice, s));
+    }
+    TC_HIP(hipEventRecord(ev.e[2], s));
+
+    // ---- 2: occupied-occupied pass of each channel (h5 split by kernel channel)
+    const bool need_occ = m.m3a2 || m.m3a4 || m.m3b2 || m.m3b5;
+    const int chunk = (P + S - 1) / S;
+    for (int sp = 0; sp < 2; ++sp) {
+      TC_HIP(hipMemsetAsync(H3[sp], 0, size_t(3) * P * NR * sizeof(cx<R>), s));
+      TC_HIP(hipMemsetAsync(H5P[sp], 0, size_t(P) * NR * sizeof(R), s));
+      TC_HIP(hipMemsetAsync(H5A[sp], 0, size_t(P) * NR * sizeof(R), s));
+    }
+    if (need_occ) {
+      for (int s2 = 0; s2 < 2; ++s2)
+        for (int a0 = 0; a0 < P; a0 += T) {
+          const int nt = std::min(T, P - a0);
+          const long npair = long(nt) * P;
+          const FusedArgs fa{P, nt, a0, S, chunk};
+          K(TC_K_XY_PAIR_OCC, fb * (npair + nt + P), [&] {
+            hipLaunchKernelGGL((k_pair_xy<R, N, true>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, PSI[s2], PSI[s2],
+                               fa, bufA.p);
+          });
+          K(TC_K_ZCONV_OCC, fb * 5.0 * npair + tabB, [&] {
+            zconv<OP_O>(s, npair, a0, mi, tb, 0);
+          });
+          K(TC_K_FUSED_O, fb * (4.0 * npair + P) + 4.5 * fb * nt * S, [&] {
+            hipLaunchKernelGGL((k_fused_O<R, N, true>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, bufB.p, PSI[s2],
+                               W[s2], fa, mi, rc, dfr.p, h5part.p, H3part.p);
+          });
+          K(TC_K_SUM_PARTS, 5.0 * fb * nt * (S + 1), [&] {
+            hipLaunchKernelGGL((k_sum_parts<R, N>), dim3(nblk(long(nt) * NR)), dim3(256), 0, s, 0, S, nt, a0, 0,
+                               h5part.p, H3part.p, nullptr, nullptr, H5P[s2], H3[s2], nullptr, nullptr);
+            hipLaunchKernelGGL((k_sum_real_parts<R, N>), dim3(nblk(long(nt) * NR)), dim3(256), 0, s, S, nt, a0,
+                               h5part.p + size_t(S) * nt * NR, H5A[s2]);
+          });
+        }
+      // M_s2 = sum w conj(H3a4) psi per channel (3b2 sources), then h6 and the 3b2 field per target spin
+      for (int s2 = 0; s2 < 2; ++s2)
+        K(TC_K_OTHER, fb * (5.0 * P + 4.0), [&] {
+          hipLaunchKernelGGL((k_reduce_occ<R, N, R>), dim3(nblk(NR)), dim3(256), 0, s, H5P[s2], H3[s2], PSI[s2], W[s2],
+                             P, LOC[s2] + 6 * NR, wk2.p + (8 + 3 * s2) * NR);
+        });
+      fft3d_t<R, N>(wk2.p + 8 * NR, 6, -1, s, pf);
+      for (int sp = 0; sp < 2; ++sp) {
+        const int o = 1 - sp;
+        K(TC_K_OTHER, fb * (2.0 * P + 1.0), [&] {
+          hipLaunchKernelGGL((k_h6_pol<R, N>), dim3(nblk(NR)), dim3(256), 0, s, H5P[sp], W[sp], H5A[o], W[o], P,
+                             LOC[sp] + 6 * NR);
+          hipLaunchKernelGGL((k_gdiv2<R, N>), dim3(nblk(NR)), dim3(256), 0, s, rc, tHUp.p, tHUa.p,
+                             wk2.p + (8 + 3 * sp) * NR, wk2.p + (8 + 3 * o) * NR, wk.p);
+        });
+        fft3d_t<R, N>(wk.p, 1, +1, s, pf);
+        TC_HIP(hipMemcpyAsync(LOC[sp] + 7 * NR, wk.p, NR * sizeof(cx<R>), hipMemcpyDeviceToDevice, s));
+      }
+    }
+    for (int sp = 0; sp < 2; ++sp)
+      K(TC_K_OTHER, 6.0 * fb * P, [&] {
+        hipLaunchKernelGGL((k_lattice3<R, N>), dim3(nblk(long(P) * NR)), dim3(256), 0, s, H3[sp], HL[sp], bm, long(P),
+                           3 * NR, NR);
+      });
+    TC_HIP(hipEventRecord(ev.e[3], s));
+
+    // ---- 3/4: target batches of each spin (partners of the same spin)
+    const bool need_A = m.m2ax || m.m2bx1 || m.m2bx2 || m.m3a3 || m.m3a4 || m.m3b4 || m.m3b6;
+    const bool need_B = m.m2bx2 || m.m3b3 || m.m3b4 || m.m3b5;
+    for (int sp = 0; sp < 2; ++sp) {
+      const int o = 1 - sp;
+      for (int t0 = 0; t0 < P; t0 += T) {
+        const int nt = std::min(T, P - t0);
+        const long npair = long(nt) * P;
+        TC_HIP(hipMemsetAsync(acc.p, 0, size_t(kAccSlots) * T * NR * sizeof(cx<double>), s));
+        TC_HIP(hipMemsetAsync(h4.p, 0, size_t(3) * T * NR * sizeof(cx<R>), s));
+        Events bev(3);
+        TC_HIP(hipEventRecord(bev.e[0], s));
+        const double part = fb * nt * S;
+        if (need_A) {
+          const FusedArgs fa{P, nt, t0, S, chunk};
+          K(TC_K_XY_PAIR_TGT, fb * (npair + nt + P), [&] {
+            hipLaunchKernelGGL((k_pair_xy<R, N, false>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, PSI[sp],
+                               PSI[sp], fa, bufA.p);
+          });
+          K(TC_K_ZCONV_A1, fb * 6.0 * npair + tabB, [&] {
+            zconv<OP_A1>(s, npair, t0, mi, tb, 1);
+          });
+          K(TC_K_FUSED_A, fb * ((m.m3b6 ? 9.0 : 5.0) * npair + 8.0 * P + nt) + 6.0 * part, [&] {
+            hipLaunchKernelGGL((k_fused_A<R, N, true>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, bufB.p, PSI[sp],
+                               DL[sp], HL[sp], NJ[sp], W[sp], fa, m, int(m.m3b6 != 0), mi, bm, mm, dfr.p, bufA.p,
+                               gpart.p, h4part.p, NJ[o]);
+          });
+          K(TC_K_SUM_PARTS, 6.0 * part + 6.0 * fd * nt + 3.0 * fb * nt, [&] {
+            hipLaunchKernelGGL((k_sum_parts<R, N>), dim3(nblk(long(nt) * NR)), dim3(256), 0, s, 1, S, nt, t0, 0,
+                               nullptr, nullptr, gpart.p, h4part.p, nullptr, nullptr, acc.p, h4.p);
+          });
+          if (m.m3b6) {
+            K(TC_K_ZCONV_A2, fb * 5.0 * npair + tabB, [&] {
+              zconv<OP_A2>(s, npair, t0, mi, tb, 1);
+            });
+            K(TC_K_FUSED_Y, fb * (npair + P) + part, [&] {
+              hipLaunchKernelGGL((k_fused_Y<R, N>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, bufB.p, PSI[sp],
+                                 W[sp], fa, 1.0, gpart.p);
+            });
+            K(TC_K_SUM_PARTS, part + 2.0 * fd * nt, [&] {
+              hipLaunchKernelGGL((k_sum_parts<R, N>), dim3(nblk(long(nt) * NR)), dim3(256), 0, s, 2, S, nt, t0, 2,
+                                 nullptr, nullptr, gpart.p, nullptr, nullptr, nullptr, acc.p, nullptr);
+            });
+          }
+        }
+        TC_HIP(hipEventRecord(bev.e[1], s));
+        if (need_B) {
+          const FusedArgs fy{P, nt, t0, S, chunk};
+          K(TC_K_OTHER, fb * 13.0 * nt, [&] {
+            hipLaunchKernelGGL((k_passB_Z<R, N>), dim3(nblk(long(nt) * NR)), dim3(256), 0, s, PSI[sp], DD[sp],
+                               LOC[sp] + NR, h4.p, t0, nt, P, m, bm, Z.p);
+          });
+          K(TC_K_XY_PASSB, fb * (2.0 * npair + 4.0 * P + 4.0 * nt), [&] {
+            hipLaunchKernelGGL((k_passB_xy<R, N>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, PSI[sp], PSI[sp], Z.p,
+                               HL[sp], fy, mi, dfr.p, R(m.m3b5), bufA.p);
+          });
+          K(TC_K_ZCONV_B, fb * 3.0 * npair + tabB, [&] {
+            zconv<OP_B>(s, npair, t0, mi, tb, 1);
+          });
+          K(TC_K_FUSED_Y, fb * (npair + P) + part, [&] {
+            hipLaunchKernelGGL((k_fused_Y<R, N>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, bufB.p, PSI[sp], W[sp],
+                               fy, 1.0, gpart.p);
+          });
+          K(TC_K_SUM_PARTS, part + 2.0 * fd * nt, [&] {
+            hipLaunchKernelGGL((k_sum_parts<R, N>), dim3(nblk(long(nt) * NR)), dim3(256), 0, s, 2, S, nt, t0, 3,
+                               nullptr, nullptr, gpart.p, nullptr, nullptr, nullptr, acc.p, nullptr);
+          });
+        }
+        TC_HIP(hipEventRecord(bev.e[2], s));
+        K(TC_K_OTHER, fb * 16.0 * nt + 8.0 * fd * nt, [&] {
+          hipLaunchKernelGGL((k_local<R, N>), dim3(nblk(long(nt) * NR)), dim3(256), 0, s, PSI[sp], DD[sp], LOC[sp],
+                             h4.p, t0, nt, P, m, acc.p, g.p);
+          hipLaunchKernelGGL((k_epart<R, N>), dim3(kAccSlots * nt), dim3(256), 0, s, PSI[sp], acc.p, t0, nt,
+                             sh.epart.p + size_t(kAccSlots) * sp * P);
+        });
+        fft3d_t<R, N>(g.p, nt, -1, s, pf);
+        K(TC_K_OTHER, 0.0, [&] {
+          hipLaunchKernelGGL((k_gather<R>), dim3(nblk(long(nt) * npm)), dim3(256), 0, s, g.p, sh.boxidx.p, sh.npw.p,
+                             nb, npm, t0, nt, 1.0 / double(NR), sh.out.p + sp * cofs, NR);
+        });
+        TC_HIP(hipEventSynchronize(bev.e[2]));
+        msA += bev.ms(0, 1);
+        msB += bev.ms(1, 2);
+      }
+    }
+    TC_HIP(hipEventRecord(ev.e[4], s));
+
+    // ---- 5: kinetic energy and FP64 corrections per channel
+    K(TC_K_CORR, 0.0, [&] {
+      for (int sp = 0; sp < 2; ++sp)
+        hipLaunchKernelGGL(k_kinetic, dim3(P), dim3(256), 0, s, sh.coef.p + sp * cofs, sh.coef.p + sp * cofs, sh.kg.p,
+                           sh.npw.p, nb, npm, sh.tkin.p + size_t(sp) * P);
+      TC_HIP(hipMemsetAsync(sh.ecorr.p, 0, size_t(4) * P * sizeof(double), s));
+      if (pb.div && (pb.mask & TC_T_CORR) && (m.m2ax || m.m3a2 || m.m3b6)) corrections_pol(s, sh, pb, m);
+    });
+    TC_HIP(hipEventRecord(ev.e[5], s));
+    TC_HIP(hipEventSynchronize(ev.e[5]));
+    if (pf && pf->on) pf->collect();
+    stage_ms[0] = ev.ms(0, 1);
+    stage_ms[1] = ev.ms(1, 2);
+    stage_ms[2] = ev.ms(2, 3);
+    stage_ms[3] = msA;
+    stage_ms[4] = msB;
+    stage_ms[5] = ev.ms(3, 5) - msA - msB;
+  }
+
+  // Spin-polarised SCF-mesh corrections (FP64): for target spin sp, 2ax with its own channel's overlaps;
+  // 3a2 summed over the partner channel s2 with A_{pair(sp, s2)} (Eqs. divcor_3a2_first/second); 3b6
+  // summed over the density channel s1 with A_{pair(s1, sp)} (Eqs. 3b6_div_scf1-3).  With identical
+  // channels this is the unpolarised form.
+  void corrections_pol(hipStream_t s, Shared& sh, const Problem& pb, const Masks& m) {
+    const int P = pb.P(), nb = pb.nb, nk = pb.nk, npm = pb.npw_max;
+    const size_t cofs = size_t(2) * P * npm;
+    cx<double>* PS64[2] = {psi64.p, psi64_1.p};
+    // per channel: overlaps, FP64 fields, n~ and Y~ (v64p: [0,1] n~, [2,3] Y~, [4] F1, [5] F2)
+    sh.S.alloc(size_t(4) * nk * nb * nb);
+    std::vector<double> Sh(size_t(4) * nk * nb * nb);
+    std::vector<double> focc2(size_t(2) * P);
+    for (int p = 0; p < P; ++p) {
+      focc2[p] = pb.occ[p];
+      focc2[P + p] = pb.occ_dn[p];
+    }
+    focc.alloc(size_t(2) * P);
+    TC_HIP(hipMemcpyAsync(focc.p, focc2.data(), focc2.size() * sizeof(double), hipMemcpyHostToDevice, s));
+    for (int sp = 0; sp < 2; ++sp) {
+      const double* cf = sh.coef.p + sp * cofs;
+      double* Ssp = sh.S.p + size_t(2) * sp * nk * nb * nb;
+      hipLaunchKernelGGL(k_overlap, dim3(nk * nb * nb), dim3(256), 0, s, cf, nb, cf, nb, sh.npw.p, npm, nk, Ssp);
+      TC_HIP(hipMemsetAsync(PS64[sp], 0, size_t(P) * NR * sizeof(cx<double>), s));
+      hipLaunchKernelGGL((k_scatter<double>), dim3(nblk(long(P) * npm)), dim3(256), 0, s, cf, sh.boxidx.p, sh.npw.p,
+                         sh.kg.p, nb, npm, P, -1, PS64[sp], NR);
+      fft3d_t<double, N>(PS64[sp], P, +1, s);
+      hipLaunchKernelGGL((k_density64<N>), dim3(nblk(NR)), dim3(256), 0, s, PS64[sp], PS64[sp], sh.w.p + sp * P, P,
+                         v64p.p + sp * NR);
+      hipLaunchKernelGGL((k_corr_Ysrc<N>), dim3(nblk(NR)), dim3(256), 0, s, PS64[sp], PS64[sp], Ssp, focc.p + sp * P,
+                         nk, nb, 1.0 / (nk * pb.omega), v64p.p + (2 + sp) * NR);
+    }
+    fft3d_t<double, N>(v64p.p, 4, -1, s);
+    TC_HIP(hipMemcpyAsync(Sh.data(), sh.S.p, Sh.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    TC_HIP(hipStreamSynchronize(s));
+    // per channel: n~(0) and sum_ab f_a f_b S(a,b) S(b,a) / Omega^2 (real in TC mode)
+    double n0[2] = {0, 0}, cs[2] = {0, 0};
+    for (int sp = 0; sp < 2; ++sp) {
+      const double* S = &Sh[size_t(2) * sp * nk * nb * nb];
+      const double* f = sp == 0 ? pb.occ.data() : pb.occ_dn.data();
+      for (int k = 0; k < nk; ++k)
+        for (int a = 0; a < nb; ++a) {
+          n0[sp] += f[k * nb + a] / nk * S[2 * ((k * nb + a) * nb + a)] / pb.omega;
+          for (int b = 0; b < nb; ++b) {
+            const double* sab = &S[2 * ((k * nb + a) * nb + b)];
+            const double* sba = &S[2 * ((k * nb + b) * nb + a)];
+            cs[sp] += f[k * nb + a] / nk * f[k * nb + b] * (sab[0] * sba[0] - sab[1] * sba[1]) / (pb.omega * pb.omega);
+          }
+        }
+    }
+    const double a0 = 2 * kPi * corrA[0] / nk, a1 = 2 * kPi * corrA[1] / nk;
+    for (int sp = 0; sp < 2; ++sp) {
+      const int o = 1 - sp;
+      const double* cf = sh.coef.p + sp * cofs;
+      const double* Ssp = sh.S.p + size_t(2) * sp * nk * nb * nb;
+      cx<double>* F1 = v64p.p + 4 * NR;
+      cx<double>* F2 = v64p.p + 5 * NR;
+      hipLaunchKernelGGL((k_corr_gfields2<N>), dim3(nblk(NR)), dim3(256), 0, s, tHu0.p, tHu1.p, a0, a1,
+                         v64p.p + sp * NR, v64p.p + o * NR, F1);
+      hipLaunchKernelGGL((k_corr_gfields2<N>), dim3(nblk(NR)), dim3(256), 0, s, tHu0.p, tHu1.p, 2 * a0, 2 * a1,
+                         v64p.p + (2 + sp) * NR, v64p.p + (2 + o) * NR, F2);
+      fft3d_t<double, N>(F1, 2, +1, s);
+      hipLaunchKernelGGL((k_corr_products<N>), dim3(nblk(2L * P * NR)), dim3(256), 0, s, F1, PS64[sp], P, prod64.p);
+      fft3d_t<double, N>(prod64.p, 2L * P, -1, s);
+      double* Zg = sh.Zg.p + sp * cofs;
+      double* Wg = sh.Wg.p + sp * cofs;
+      hipLaunchKernelGGL((k_gather<double>), dim3(nblk(long(P) * npm)), dim3(256), 0, s, prod64.p, sh.boxidx.p,
+                         sh.npw.p, nb, npm, 0, P, 1.0 / double(NR), Zg, NR);
+      hipLaunchKernelGGL((k_gather<double>), dim3(nblk(long(P) * npm)), dim3(256), 0, s, prod64.p + size_t(P) * NR,
+                         sh.boxidx.p, sh.npw.p, nb, npm, 0, P, 1.0 / double(NR), Wg, NR);
+      hipLaunchKernelGGL(k_overlap, dim3(nk * nb * nb), dim3(256), 0, s, cf, nb, Zg, nb, sh.npw.p, npm, nk, sh.O.p);
+      // channel prefactors: pair(sp, sp) = parallel, pair(sp, o) = antiparallel
+      const double c1a_p = kFourPi * corrB[0], c1a_a = kFourPi * corrB[1];
+      const double c1s_p = 2 * kPi * corrB[0], c1s_a = 2 * kPi * corrB[1];
+      const double const1 = c1a_p * cs[sp] + c1a_a * cs[o];
+      const double c1sn0 = c1s_p * n0[sp] + c1s_a * n0[o];
+      hipLaunchKernelGGL(k_corr_apply, dim3(nblk(long(P) * npm)), dim3(256), 0, s, cf, cf, Ssp, sh.O.p, Zg, Wg,
+                         focc.p + sp * P, sh.npw.p, nb, nb, npm, P, pb.omega, m.m2ax, pb.delta_gb, m.m3a2, const1, 0.0,
+                         m.m3b6, c1sn0, 0.0, sh.dhc2.p + sp * cofs, sh.dhc3.p + sp * cofs);
+      hipLaunchKernelGGL(k_corr_add, dim3(P), dim3(256), 0, s, cf, sh.dhc2.p + sp * cofs, sh.dhc3.p + sp * cofs,
+                         sh.npw.p, nb, npm, sh.out.p + sp * cofs, sh.ecorr.p + size_t(2) * sp * P);
+    }
+  }
+
   // SCF-mesh divergence corrections in FP64 (2ax, 3a2, 3b6); see k_corr_apply.
   // Biorthogonal mode: overlaps S(a,b) = <chi_a|psi_b>, densities and 3a2 sources with conj(chi),
   // energies with <chi|.
@@ -1544,6 +1943,12 @@ int prepare(tc_ctx* c) {
   if (nleft != 0 && nleft != pb.nk)
     return fail(c, TC_ERR_STATE, "left orbitals are loaded for some k-points only");
   pb.bitc = nleft == pb.nk;
+  if (pb.nspin == 2) {
+    for (int k = 0; k < pb.nk; ++k)
+      if (!pb.loaded_dn[k])
+        return fail(c, TC_ERR_STATE, "down-spin orbitals of k-point " + std::to_string(k) + " not loaded");
+    if (pb.bitc) return fail(c, TC_ERR_UNSUPPORTED, "spin-polarised runs are built for TC mode (no left orbitals)");
+  }
   if (!c->eng || c->eng_prec != pb.prec || c->eng_N != pb.N) {
     if (pb.prec == TC_PREC_FP32_SPLITBF16 && pb.N % 8 != 0)
       return fail(c, TC_ERR_UNSUPPORTED, "split-BF16 DFT stages need a grid length divisible by 8");
@@ -1566,13 +1971,15 @@ void finish_energy(tc_ctx* c) {
   Problem& pb = c->pb;
   const int P = pb.P();
   const Masks m = make_masks(pb.mask);
-  std::vector<double> ep(size_t(kAccSlots) * P), tk(P), ec(size_t(2) * P);
+  const int ns = pb.nspin;
+  std::vector<double> ep(size_t(kAccSlots) * ns * P), tk(size_t(ns) * P), ec(size_t(2) * ns * P);
   TC_HIP(hipMemcpy(ep.data(), c->sh.epart.p, ep.size() * sizeof(double), hipMemcpyDeviceToHost));
   TC_HIP(hipMemcpy(tk.data(), c->sh.tkin.p, tk.size() * sizeof(double), hipMemcpyDeviceToHost));
   TC_HIP(hipMemcpy(ec.data(), c->sh.ecorr.p, ec.size() * sizeof(double), hipMemcpyDeviceToHost));
   double T = 0, E2 = 0, E3 = 0, EC = 0;
-  for (int p = 0; p < P; ++p) {
-    const double f = pb.occ[p] * 2.0 / pb.nk;   // both spin channels
+  for (int p = 0; p < ns * P; ++p) {
+    // unpolarised: both spin channels (factor 2); polarised: each channel with its own fillings
+    const double f = ns == 1 ? pb.occ[p] * 2.0 / pb.nk : (p < P ? pb.occ[p] : pb.occ_dn[p - P]) / pb.nk;
     const double* e = &ep[size_t(kAccSlots) * p];
     T += f * tk[p];
     // Two-body terms count 1/2, three-body terms 1/3 (multiplicities are in the operator).  Pass B (slot 3)
@@ -1596,7 +2003,7 @@ void finish_energy(tc_ctx* c) {
 void alloc_shared(tc_ctx* c) {
   Problem& pb = c->pb;
   Shared& sh = c->sh;
-  const int P = pb.P();
+  const int P = pb.nspin * pb.P();   // orbitals of all spin channels
   sh.out.alloc(size_t(2) * P * pb.npw_max);
   sh.dhc2.alloc(size_t(2) * P * pb.npw_max);
   sh.dhc3.alloc(size_t(2) * P * pb.npw_max);
@@ -1613,14 +2020,18 @@ void alloc_shared(tc_ctx* c) {
 void run_apply(tc_ctx* c, void* out_dev, double* out_host) {
   Problem& pb = c->pb;
   Shared& sh = c->sh;
-  const int P = pb.P();
+  const int P = pb.nspin * pb.P();   // orbitals of all spin channels (spin-major)
   alloc_shared(c);
   c->eng->prof = &c->prof;
   c->eng->apply(c->stream, sh, pb, c->stage_ms);
   c->total_ms = 0;
   for (double v : c->stage_ms) c->total_ms += v;
-  hipLaunchKernelGGL(k_orbital_eps, dim3(P), dim3(256), 0, c->stream, pb.bitc ? sh.coefL.p : sh.coef.p, sh.coef.p,
-                     sh.out.p, sh.kg.p, sh.npw.p, pb.nb, pb.npw_max, sh.eps.p);
+  for (int sp = 0; sp < pb.nspin; ++sp) {
+    const size_t co = size_t(2) * sp * pb.P() * pb.npw_max;
+    hipLaunchKernelGGL(k_orbital_eps, dim3(pb.P()), dim3(256), 0, c->stream, (pb.bitc ? sh.coefL.p : sh.coef.p) + co,
+                       sh.coef.p + co, sh.out.p + co, sh.kg.p, sh.npw.p, pb.nb, pb.npw_max,
+                       sh.eps.p + size_t(2) * sp * pb.P());
+  }
   c->eps.resize(size_t(2) * P);
   TC_HIP(hipMemcpyAsync(c->eps.data(), sh.eps.p, c->eps.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
   if (out_dev)
@@ -1644,6 +2055,7 @@ int do_apply(tc_ctx* c, void* out_dev, double* out_host) {
 // The operator of the loaded orbitals applied to nvec trial vectors per k-point (device in/out).
 int do_apply_vectors(tc_ctx* c, int nvec, const double* in_dev, double* out_dev) {
   if (nvec <= 0) return fail(c, TC_ERR_ARG, "nvec must be positive");
+  if (c->pb.nspin == 2) return fail(c, TC_ERR_UNSUPPORTED, "trial vectors are built for unpolarised runs");
   int st = prepare(c);
   if (st != TC_OK) return st;
   alloc_shared(c);
@@ -1682,6 +2094,7 @@ int do_backward(tc_ctx* c, void* grad_dev, double* grad_host, double* dA, double
     return fail(c, TC_ERR_UNSUPPORTED, "the gradient of the grad-u . grad terms needs 2ah and 2ax selected");
   int st = prepare(c);
   if (st != TC_OK) return st;
+  if (pb.nspin == 2) return fail(c, TC_ERR_UNSUPPORTED, "the gradient is built for unpolarised runs");
   if (!pb.bitc && (gl_dev || gl_host)) return fail(c, TC_ERR_ARG, "no left orbitals loaded: grad_left must be NULL");
   struct Keep {
     tc_ctx* c;
@@ -1794,16 +2207,18 @@ void upload_basis_data(tc_ctx* c) {
   c->sh.boxidx.alloc(box.size());
   c->sh.kg.alloc(kg.size());
   c->sh.npw.alloc(pb.nk);
-  c->sh.w.alloc(P);
-  std::vector<double> w(P);
+  c->sh.w.alloc(size_t(pb.nspin) * P);
+  std::vector<double> w(size_t(pb.nspin) * P);
   for (int p = 0; p < P; ++p) w[p] = pb.occ[p] / pb.nk;
+  if (pb.nspin == 2)
+    for (int p = 0; p < P; ++p) w[P + p] = pb.occ_dn[p] / pb.nk;
   TC_HIP(hipMemcpy(c->sh.boxidx.p, box.data(), box.size() * sizeof(int), hipMemcpyHostToDevice));
   TC_HIP(hipMemcpy(c->sh.kg.p, kg.data(), kg.size() * sizeof(double), hipMemcpyHostToDevice));
   TC_HIP(hipMemcpy(c->sh.npw.p, pb.npw.data(), pb.nk * sizeof(int), hipMemcpyHostToDevice));
-  TC_HIP(hipMemcpy(c->sh.w.p, w.data(), P * sizeof(double), hipMemcpyHostToDevice));
+  TC_HIP(hipMemcpy(c->sh.w.p, w.data(), w.size() * sizeof(double), hipMemcpyHostToDevice));
 }
 
-int begin_load(tc_ctx* c, int ik, int nband, const double* occ) {
+int begin_load(tc_ctx* c, int ik, int nband, const double* occ, int spin = 0) {
   Problem& pb = c->pb;
   if (pb.nk == 0 || pb.N == 0) return fail(c, TC_ERR_STATE, "set the k-mesh and grid before loading orbitals");
   if (ik < 0 || ik >= pb.nk) return fail(c, TC_ERR_ARG, "k-point index out of range");
@@ -1816,17 +2231,21 @@ int begin_load(tc_ctx* c, int ik, int nband, const double* occ) {
   if (pb.nb != nband) {
     if (pb.nb != 0)
       for (int k = 0; k < pb.nk; ++k)
-        if (pb.loaded[k] && k != ik) return fail(c, TC_ERR_ARG, "nband differs between k-points");
+        if ((pb.loaded[k] && (k != ik || spin != 0)) || (pb.nspin == 2 && pb.loaded_dn[k] && (k != ik || spin != 1)))
+          return fail(c, TC_ERR_ARG, "nband differs between k-points or spin channels");
     pb.nb = nband;
     pb.occ.assign(size_t(pb.nk) * nband, 0.0);
+    pb.occ_dn.assign(size_t(pb.nk) * nband, 0.0);
     std::fill(pb.loaded.begin(), pb.loaded.end(), 0);
     std::fill(pb.left.begin(), pb.left.end(), 0);
+    std::fill(pb.loaded_dn.begin(), pb.loaded_dn.end(), 0);
   }
   int mx = 0;
   for (int k = 0; k < pb.nk; ++k) mx = std::max(mx, pb.npw[k]);
   pb.npw_max = mx;
-  c->sh.coef.alloc(size_t(2) * pb.P() * pb.npw_max);
-  for (int b = 0; b < nband; ++b) pb.occ[size_t(ik) * nband + b] = occ[b];
+  c->sh.coef.alloc(size_t(2) * pb.nspin * pb.P() * pb.npw_max);   // spin-major: spin 0 first
+  double* o = spin == 0 ? pb.occ.data() : pb.occ_dn.data();
+  for (int b = 0; b < nband; ++b) o[size_t(ik) * nband + b] = occ[b];
   return TC_OK;
 }
 
@@ -1901,6 +2320,7 @@ int do_scf(tc_ctx* c, const tc_scf_params& prm, double* ehist, int* niter) {
                 "scf parameters out of range (max_iter >= 1, 0 <= pmax <= 16, etol > 0, 0 < mix <= 1)");
   int st = prepare(c);
   if (st != TC_OK) return st;
+  if (c->pb.nspin == 2) return fail(c, TC_ERR_UNSUPPORTED, "the self-consistent loop is built for unpolarised runs");
   Problem& pb = c->pb;
   Shared& sh = c->sh;
   hipStream_t s = c->stream;
@@ -2111,6 +2531,7 @@ int tc_set_kmesh(tc_ctx* c, int n1, int n2, int n3) {
     pb.npw.assign(pb.nk, 0);
     pb.loaded.assign(pb.nk, 0);
     pb.left.assign(pb.nk, 0);
+    pb.loaded_dn.assign(pb.nk, 0);
     pb.nb = 0;
     c->tables_dirty = true;
     c->have_result = false;
@@ -2206,6 +2627,46 @@ int tc_load_orbitals(tc_ctx* c, int ik, int nband, const double* right, const do
       pb.left[ik] = 1;
     }
     pb.loaded[ik] = 1;
+    return TC_OK;
+  });
+}
+
+int tc_set_nspin(tc_ctx* c, int nspin) {
+  return guard(c, [&]() -> int {
+    if (nspin != 1 && nspin != 2) return fail(c, TC_ERR_ARG, "nspin must be 1 or 2");
+    Problem& pb = c->pb;
+    if (pb.nk == 0) return fail(c, TC_ERR_STATE, "set the k-mesh before the number of spin channels");
+    pb.nspin = nspin;
+    pb.nb = 0;   // every channel is loaded again
+    std::fill(pb.loaded.begin(), pb.loaded.end(), 0);
+    std::fill(pb.left.begin(), pb.left.end(), 0);
+    pb.loaded_dn.assign(pb.nk, 0);
+    c->have_result = false;
+    return TC_OK;
+  });
+}
+
+int tc_load_orbitals_spin(tc_ctx* c, int spin, int ik, int nband, const double* right, const double* left,
+                          const double* occ) {
+  if (spin == 0) return tc_load_orbitals(c, ik, nband, right, left, occ);
+  return guard(c, [&]() -> int {
+    Problem& pb = c->pb;
+    if (spin != 1) return fail(c, TC_ERR_ARG, "spin must be 0 or 1");
+    if (pb.nspin != 2) return fail(c, TC_ERR_STATE, "tc_set_nspin(ctx, 2) first");
+    if (left) return fail(c, TC_ERR_UNSUPPORTED, "spin-polarised runs are built for TC mode (no left orbitals)");
+    if (!right) return fail(c, TC_ERR_ARG, "null coefficients");
+    int st = begin_load(c, ik, nband, occ, 1);
+    if (st != TC_OK) return st;
+    const int npw = pb.npw[ik];
+    pb.loaded_dn[ik] = 0;
+    c->have_result = false;
+    std::vector<double> stage(size_t(2) * nband * pb.npw_max, 0.0);
+    for (int b = 0; b < nband; ++b)
+      std::memcpy(&stage[size_t(2) * b * pb.npw_max], right + size_t(2) * b * npw, size_t(2) * npw * sizeof(double));
+    TC_HIP(hipMemcpy(c->sh.coef.p + size_t(2) * (pb.P() + size_t(ik) * nband) * pb.npw_max, stage.data(),
+                     stage.size() * sizeof(double), hipMemcpyHostToDevice));
+    upload_basis_data(c);
+    pb.loaded_dn[ik] = 1;
     return TC_OK;
   });
 }

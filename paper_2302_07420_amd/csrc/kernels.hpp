@@ -241,6 +241,59 @@ __global__ void k_mul_vec_scalar(const cx<R>* v, const cx<R>* s, cx<R>* out) {
   for (int c = 0; c < 3; ++c) out[c * NR + r] = v[c * NR + r] * s[r];
 }
 
+// Spin-polarised Hartree-type fields for target spin s: the parallel-channel kernels act on the own
+// spin's densities (nG, JG), the antiparallel ones on the other spin's (nGo, JGo).
+//   out: VH~, h1~ x3, P~ (as k_hartree_g)
+template <typename R, int N>
+__global__ void k_hartree_g2(const Recip rc, const R* tVp, const R* tVa, const R* tUp, const R* tUa, const cx<R>* nG,
+                             const cx<R>* JG, const cx<R>* nGo, const cx<R>* JGo, cx<R>* out) {
+  constexpr long NR = long(N) * N * N;
+  const long r = long(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (r >= NR) return;
+  const int x = int(r % N), y = int((r / N) % N), z = int(r / (N * N));
+  const double zero[3] = {0, 0, 0};
+  R Q[3];
+  qvec<R, N>(rc, zero, x, y, z, Q);
+  const cx<R> n1 = nG[r], n2 = nGo[r];
+  out[r] = tVp[r] * n1 + tVa[r] * n2;
+  const cx<R> un = tUp[r] * n1 + tUa[r] * n2;
+  cx<R> p = mk<R>(R(0), R(0));
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    out[(1 + c) * NR + r] = mul_i(Q[c] * un);
+    p = p + mul_i((-Q[c]) * (tUp[r] * JG[c * NR + r] + tUa[r] * JGo[c * NR + r]));
+  }
+  out[4 * NR + r] = p;
+}
+
+// out~ = sum_c -i G_c (u_par in~_c + u_anti ino~_c)  (spin-polarised form of k_gdiv)
+template <typename R, int N>
+__global__ void k_gdiv2(const Recip rc, const R* tUp, const R* tUa, const cx<R>* in, const cx<R>* ino, cx<R>* out) {
+  constexpr long NR = long(N) * N * N;
+  const long r = long(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (r >= NR) return;
+  const int x = int(r % N), y = int((r / N) % N), z = int(r / (N * N));
+  const double zero[3] = {0, 0, 0};
+  R Q[3];
+  qvec<R, N>(rc, zero, x, y, z, Q);
+  cx<R> p = mk<R>(R(0), R(0));
+#pragma unroll
+  for (int c = 0; c < 3; ++c) p = p + mul_i((-Q[c]) * (tUp[r] * in[c * NR + r] + tUa[r] * ino[c * NR + r]));
+  out[r] = p;
+}
+
+// h6 of target spin s (Alg. 3a2, spin-polarised): sum over own-spin partners of the parallel-channel h5
+// and over other-spin partners of the antiparallel-channel h5
+template <typename R, int N>
+__global__ void k_h6_pol(const R* h5p, const double* w, const R* h5ao, const double* wo, int P, cx<R>* h6) {
+  constexpr long NR = long(N) * N * N;
+  const long r = long(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (r >= NR) return;
+  double s = 0;
+  for (int a = 0; a < P; ++a) s += w[a] * double(h5p[long(a) * NR + r]) + wo[a] * double(h5ao[long(a) * NR + r]);
+  h6[r] = mk<R>(R(s), R(0));
+}
+
 // ---------------------------------------------------------------- pair passes
 // Lattice components of the vector kernel.  With kappa_d = m_d + delta_d (grid frequency plus the
 // pair's shift Delta, both in units of the reciprocal rows b_d), Q_c = sum_d kappa_d B_dc.  The
@@ -854,12 +907,13 @@ struct PassA {
   static constexpr int NPL = SPLIT ? 4 : 7;
 };
 
-template <typename R, int N>
+// POL (spin-polarised runs): the antiparallel-channel 3b6 sources take the other spin's density nA.
+template <typename R, int N, bool POL = false>
 __global__ void __launch_bounds__((Fz<R, N>::NTH)) k_fused_A(const cx<R>* buf5, const cx<R>* psi, const cx<R>* Dl,
                                                            const cx<R>* Hl, const cx<R>* n, const double* w,
                                                            FusedArgs fa, Masks m, int do3b6, MeshInfo mi,
                                                            Basis<R> B, Basis<R> M, const double* dfr, cx<R>* src4,
-                                                           cx<R>* gpart, cx<R>* h4part) {
+                                                           cx<R>* gpart, cx<R>* h4part, const cx<R>* nA = nullptr) {
   using F = Fz<R, N>;
   constexpr int KP = F::KP, RB = F::RB, PL = F::PLANE;
   constexpr bool SPLIT = PassA<R, N>::SPLIT;
@@ -867,7 +921,7 @@ __global__ void __launch_bounds__((Fz<R, N>::NTH)) k_fused_A(const cx<R>* buf5, 
   __shared__ cx<R> sm[PassA<R, N>::NPL * PL];
   const PlaneWG<R, N> wg(fa);
   const int jt = fa.t0 + wg.t;
-  cx<R> ga[KP][3], h4[KP][3], nk[KP];
+  cx<R> ga[KP][3], h4[KP][3], nk[KP], na[POL ? KP : 1];
   unsigned ob[KP];   // byte offsets of the owned points within a volume
 #pragma unroll
   for (int i = 0; i < KP; ++i) ob[i] = (wg.zo + RB * N * i) * unsigned(sizeof(cx<R>));
@@ -876,6 +930,7 @@ __global__ void __launch_bounds__((Fz<R, N>::NTH)) k_fused_A(const cx<R>* buf5, 
 #pragma unroll
     for (int s = 0; s < 3; ++s) ga[i][s] = h4[i][s] = mk<R>(R(0), R(0));
     nk[i] = ldo(n, ob[i]);
+    if constexpr (POL) na[i] = ldo(nA, ob[i]);
   }
   // 2bx1 is accumulated (into its own slot) whenever 2bx1 or 2bx2 is selected: its bracket is also the
   // energy of 2bx2, which pass B fuses with three-body terms
@@ -954,8 +1009,13 @@ __global__ void __launch_bounds__((Fz<R, N>::NTH)) k_fused_A(const cx<R>* buf5, 
 #pragma unroll
           for (int d = 0; d < 3; ++d) Y[d] = sm[(ab + d) * PL + so];
           apply_metric(M, Y, T);
+          cx<R> nanti;
+          if constexpr (POL)
+            nanti = na[i];
+          else
+            nanti = nk[i];
 #pragma unroll
-          for (int d = 0; d < 3; ++d) sm[(ab + d) * PL + so] = T[d] * nk[i];
+          for (int d = 0; d < 3; ++d) sm[(ab + d) * PL + so] = T[d] * nanti;
         }
       }
       __syncthreads();
@@ -1041,7 +1101,10 @@ struct PassO {
   static constexpr int NPL = SPLIT ? 3 : 6;
 };
 
-template <typename R, int N>
+// SPLITH (spin-polarised runs): the parallel- and antiparallel-channel parts of h5 are kept apart, the
+// antiparallel one in the second half of h5part ([2][S][T][N^3]); they serve targets of the partners' own
+// spin and of the other spin respectively.
+template <typename R, int N, bool SPLITH = false>
 __global__ void __launch_bounds__((Fz<R, N>::NTH)) k_fused_O(const cx<R>* buf4, const cx<R>* psi, const double* w,
                                                            FusedArgs fa, MeshInfo mi, Recip rc, const double* dfr,
                                                            R* h5part, cx<R>* H3part) {
@@ -1053,11 +1116,12 @@ __global__ void __launch_bounds__((Fz<R, N>::NTH)) k_fused_O(const cx<R>* buf4, 
   const PlaneWG<R, N> wg(fa);
   const Basis<R> B = basis<R>(rc);
   const int ja = fa.t0 + wg.t;
-  R h5[KP];
+  R h5[KP], h5b[SPLITH ? KP : 1];
   cx<R> H[KP][3];
 #pragma unroll
   for (int i = 0; i < KP; ++i) {
     h5[i] = R(0);
+    if constexpr (SPLITH) h5b[i] = R(0);
     H[i][0] = H[i][1] = H[i][2] = mk<R>(R(0), R(0));
   }
   // the next partner's four pair planes are loaded into registers while this partner is transformed
@@ -1124,7 +1188,13 @@ __global__ void __launch_bounds__((Fz<R, N>::NTH)) k_fused_O(const cx<R>* buf4, 
           for (int d = 0; d < 3; ++d) Y[d] = sm[(ab + d) * PL + so];
           to_cart(B, Y, X);
 #pragma unroll
-          for (int cd = 0; cd < 3; ++cd) h5[i] += wq * (X[cd].x * X[cd].x + X[cd].y * X[cd].y);
+          for (int cd = 0; cd < 3; ++cd) {
+            const R v = wq * (X[cd].x * X[cd].x + X[cd].y * X[cd].y);
+            if constexpr (SPLITH)
+              h5b[i] += v;
+            else
+              h5[i] += v;
+          }
         }
       }
       __syncthreads();
@@ -1134,6 +1204,7 @@ __global__ void __launch_bounds__((Fz<R, N>::NTH)) k_fused_O(const cx<R>* buf4, 
   for (int i = 0; i < KP; ++i) {
     const long r = wg.zo + RB * N * i;
     h5part[(long(wg.c) * fa.T + wg.t) * NR + r] = h5[i];
+    if constexpr (SPLITH) h5part[(long(fa.S + wg.c) * fa.T + wg.t) * NR + r] = h5b[i];
 #pragma unroll
     for (int cd = 0; cd < 3; ++cd) H3part[((long(wg.c) * fa.T + wg.t) * 3 + cd) * NR + r] = H[i][cd];
   }
@@ -1271,6 +1342,19 @@ __global__ void __launch_bounds__((Fz<R, N>::NTH)) k_fused_OB(const cx<R>* buf21
       Hbpart[(o * 3 + c) * NR + r] = Hb[i][c];
     }
   }
+}
+
+// Fixed-order FP64 sum of real partner-chunk partials: out[t0 + t] = sum_c parts[c][t]
+template <typename R, int N>
+__global__ void k_sum_real_parts(int S, int T, int t0, const R* parts, R* out) {
+  constexpr long NR = long(N) * N * N;
+  const long id = long(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (id >= long(T) * NR) return;
+  const int t = int(id / NR);
+  const long r = id - long(t) * NR;
+  double s = 0;
+  for (int c = 0; c < S; ++c) s += double(parts[(long(c) * T + t) * NR + r]);
+  out[long(t0 + t) * NR + r] = R(s);
 }
 
 // Fixed-order FP64 sums of the partials of k_fused_OB: h5[t0+t], H3a4[t0+t], H3bc[t0+t].

@@ -19,7 +19,8 @@ def declared():
 def test_header_declares_the_boundary():
     names = declared()
     for must in ("tc_create", "tc_set_cell", "tc_set_kmesh", "tc_set_grid", "tc_set_basis", "tc_set_jastrow",
-                 "tc_load_orbitals", "tc_apply_all", "tc_energy", "tc_orbital_energies", "tc_energy_backward"):
+                 "tc_load_orbitals", "tc_apply_all", "tc_energy", "tc_orbital_energies", "tc_energy_backward",
+                 "tc_apply", "tc_scf", "tc_set_nspin", "tc_load_orbitals_spin"):
         assert must in names
 
 

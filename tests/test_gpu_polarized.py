@@ -1,0 +1,158 @@
+"""Spin-polarised TC mode of the HIP path through the C ABI: each spin channel has its own orbitals.
+
+Against the FP64 oracle on the same inputs: every term of both spin channels, the totals, the energy
+and its parts, and the orbital energies of both channels (FP64 and FP32).  Independent of the oracle:
+two identical channels reproduce the unpolarised run, and exchanging the channels exchanges the
+outputs and keeps the energy.  The unsupported calls with two channels fail with TC_ERR_UNSUPPORTED.
+"""
+import numpy as np
+import pytest
+
+import tcinputs as T
+from oracle.fftroute import ALL_TERMS, MULT, Problem
+
+pytestmark = pytest.mark.gpu
+
+tc = pytest.importorskip("paper_2302_07420_amd")
+
+FP64_TOL = 1e-10
+FP32_TOL = 2e-6
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def relerr(a, b):
+    scale = max(np.abs(x).max() for x in b)
+    return max(np.abs(x - y).max() for x, y in zip(a, b)) / scale
+
+
+CASES = {
+    "fcc_k211_g8_pol": lambda: T.polarized(T.tiny_fcc(kmesh=(2, 1, 1), grid=8, ecut=2.0, nb=2, a=6.0,
+                                                      occ=[1.0, 0.7]), 31, occ_dn=[0.9, 0.2]),
+    "fcc_k221_g12_pol_empty_band": lambda: T.polarized(T.tiny_fcc(kmesh=(2, 2, 1), grid=12, ecut=2.0, nb=3, a=6.0,
+                                                                  occ=[1.0, 0.8, 0.3], seed_offset=5), 33,
+                                                       occ_dn=[1.0, 0.0, 0.0]),
+    "fcc_k121_g16_pol": lambda: T.polarized(T.tiny_fcc(kmesh=(1, 2, 1), grid=16, ecut=3.0, nb=2, a=7.0,
+                                                       seed_offset=9), 34, mix=0.5),
+}
+
+
+@pytest.fixture(scope="module", params=list(CASES))
+def case(request):
+    w = CASES[request.param]()
+    pr = Problem(w)
+    assert pr.polarized
+    per = {s: {t: [c.numpy() for c in pr.to_coeff(MULT.get(t, 1) * pr.term(t, s), s)] for t in ALL_TERMS}
+           for s in (0, 1)}
+    tot = {s: [sum(per[s][t][k] for t in ALL_TERMS) for k in range(w.nk)] for s in (0, 1)}
+    E, parts = pr.energy(per_term=True)
+    eps = np.stack([(pr.kinetic(s) + pr.braket(s, sum(MULT.get(t, 1) * pr.term(t, s) for t in ALL_TERMS)))
+                    .numpy().reshape(w.nk, -1) for s in (0, 1)])
+    return request.param, w, per, tot, float(E), {k: float(v) for k, v in parts.items()}, eps
+
+
+def test_every_term_fp64(case):
+    name, w, per, tot, *_ = case
+    for t in ALL_TERMS:
+        _say(f"[gpu] polarised {name} fp64 term {t}")
+        op = tc.from_workload(w, precision=tc.TC_PREC_FP64, terms=tc.TERM_BITS[t] | tc.TERM_BITS["corr"])
+        got = op.apply()
+        op.close()
+        for s in (0, 1):
+            scale = max(np.abs(x).max() for x in tot[s])
+            err = max(np.abs(g - r).max() for g, r in zip(got[s], per[s][t])) / scale
+            assert err < FP64_TOL, (t, s, err)
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", FP64_TOL), ("fp32", FP32_TOL)])
+def test_total_energy_and_orbital_energies(case, prec, tol):
+    name, w, per, tot, E, parts, eps = case
+    _say(f"[gpu] polarised {name} {prec} total")
+    op = tc.from_workload(w, precision=tc.TC_PREC_FP64 if prec == "fp64" else tc.TC_PREC_FP32)
+    got = op.apply()
+    Eg, pg = op.energy()
+    eg = op.orbital_energies()
+    op.close()
+    for s in (0, 1):
+        err = relerr(got[s], tot[s])
+        _say(f"    spin {s}: max |H c - oracle| / max = {err:.3e}")
+        assert err < tol, (s, err)
+    assert abs(Eg - E) < tol * abs(E), (Eg, E)
+    assert abs(pg["kinetic"] - parts["T"]) < tol * abs(E)
+    e2 = sum(parts[t] for t in ALL_TERMS if t.startswith("2"))
+    e3 = sum(parts[t] for t in ALL_TERMS if t.startswith("3"))
+    assert abs(pg["two_body"] - e2) < tol * abs(E), (pg["two_body"], e2)
+    assert abs(pg["three_body"] - e3) < tol * abs(E), (pg["three_body"], e3)
+    assert eg.shape == eps.shape
+    erre = np.abs(eg - eps).max() / np.abs(eps).max()
+    _say(f"    orbital energies: {erre:.3e}")
+    assert erre < tol
+
+
+def test_identical_channels_reproduce_unpolarized():
+    """Both channels loaded with the same orbitals and fillings: the unpolarised run's outputs."""
+    w = T.tiny_fcc(kmesh=(2, 2, 1), grid=12, ecut=2.0, nb=3, a=6.0, occ=[1.0, 0.9, 0.0])
+    _say("[gpu] polarised identical channels fcc_k221_g12")
+    op = tc.from_workload(w, precision=tc.TC_PREC_FP64)
+    ref = op.apply()
+    E0, p0 = op.energy()
+    e0 = op.orbital_energies()
+    op.close()
+    wp = w.replace(right_dn=list(w.right), occ_dn=list(w.occ))
+    op = tc.from_workload(wp, precision=tc.TC_PREC_FP64)
+    got = op.apply()
+    E1, p1 = op.energy()
+    e1 = op.orbital_energies()
+    op.close()
+    for s in (0, 1):
+        assert relerr(got[s], ref) < 1e-12
+        assert np.abs(e1[s] - e0).max() < 1e-12 * np.abs(e0).max()
+    assert abs(E1 - E0) < 1e-12 * abs(E0)
+
+
+def test_exchanging_channels_exchanges_outputs():
+    w = T.polarized(T.tiny_fcc(kmesh=(2, 1, 1), grid=8, ecut=2.0, nb=2, a=6.0, occ=[1.0, 0.7]), 9,
+                    occ_dn=[0.8, 0.1])
+    ws = w.replace(right=w.right_dn, right_dn=w.right, occ=w.occ_dn, occ_dn=w.occ)
+    _say("[gpu] polarised channel exchange fcc_k211_g8")
+    outs, Es = [], []
+    for x in (w, ws):
+        op = tc.from_workload(x, precision=tc.TC_PREC_FP64)
+        outs.append(op.apply())
+        Es.append(op.energy()[0])
+        op.close()
+    assert abs(Es[1] - Es[0]) < 1e-12 * abs(Es[0])
+    for s in (0, 1):
+        assert relerr(outs[1][1 - s], outs[0][s]) < 1e-12
+
+
+def test_unsupported_calls_with_two_channels():
+    w = T.polarized(T.tiny_fcc(kmesh=(2, 1, 1), grid=8, ecut=2.0, nb=2, a=6.0, occ=[1.0, 0.7]), 9)
+    _say("[gpu] polarised unsupported calls")
+    op = tc.from_workload(w, precision=tc.TC_PREC_FP64)
+    with pytest.raises(tc.TCError, match="status"):
+        op.apply_vectors([np.zeros((1, n), complex) for n in op.npw])
+    with pytest.raises(tc.TCError, match="status"):
+        op.scf(max_iter=2)
+    with pytest.raises(tc.TCError, match="status"):
+        op.backward()
+    with pytest.raises(tc.TCError, match="status"):   # left orbitals in a polarised channel
+        op.load_orbitals(0, w.right_dn[0], w.occ_dn[0], left=w.right_dn[0], spin=1)
+    op.close()
+    # a missing down channel is reported before any work
+    op = tc.TCOperator()
+    op.set_cell(w.lattice)
+    op.set_kmesh(*w.kmesh)
+    op.set_grid(*w.grid)
+    for ik, m in enumerate(w.miller):
+        op.set_basis(ik, m)
+    op.set_jastrow(w.A, w.C)
+    op.set_options(tc.TC_PREC_FP64, w.alpha, True, tc.TERM_ALL)
+    op.set_nspin(2)
+    for ik in range(w.nk):
+        op.load_orbitals(ik, w.right[ik], w.occ[ik])
+    with pytest.raises(tc.TCError, match="status"):
+        op.apply()
+    op.close()
