@@ -157,6 +157,28 @@ int tc_load_orbitals_dev(tc_ctx* ctx, int ik, int nband, const void* right_dev, 
  * TC_ERR_ARG unless nspin is 1 or 2; TC_ERR_STATE before the k-mesh. */
 int tc_set_nspin(tc_ctx* ctx, int nspin);
 
+/* Crystal symmetry (Sec. 2.6.1: the orbital of k = R^T k0 - b is the image of that of k0; Sec. 2.6.4: the
+ * fields h5 and h3 of the occupied-occupied pass of Algs. 3a2 and 3a4 are computed for irreducible
+ * k-points only and rotated).  nsym operations x -> R (x + tau) on fractional (lattice) coordinates x:
+ * rot holds nsym row-major integer 3x3 matrices R, tau nsym fractional translations.  Each operation must
+ * be an isometry of the lattice, map the k-mesh onto itself and the grid onto itself (N tau integer), and
+ * together they must form a group (TC_ERR_ARG otherwise).  nsym = 0 switches symmetry off.
+ *
+ * The representative of each k-point is the lowest k index of its orbit.  Only the representatives'
+ * orbitals need to be loaded: at the next application the library replaces the orbitals and fillings
+ * of every other k-point k with the image, under the first listed operation that carries its
+ * representative k0 onto k, of k0's orbitals: c_k(m) = c_k0(m0) exp(2 pi i (m - b).tau) with
+ * m = R^T m0 + b, so that u_k(x) = exp(2 pi i b.x) u_k0(R (x + tau)).  It checks that every
+ * representative's plane-wave set and weighted occupied set are invariant under the operations that fix
+ * its k-point (TC_ERR_ARG otherwise): then the operator and energy equal those of the full calculation on
+ * the generated set.  The occupied-occupied pass and the target passes then run for the
+ * representatives' orbitals only; the other orbitals' fields, outputs and energy contributions follow by
+ * the operations.  tc_get_orbitals returns the generated orbitals after an application.
+ * Built for TC mode with one spin channel (TC_ERR_UNSUPPORTED at application otherwise); tc_apply*,
+ * tc_scf and tc_energy_backward* return TC_ERR_UNSUPPORTED while symmetry is set.  Call after the cell,
+ * k-mesh and grid (TC_ERR_STATE otherwise); setting any of them again switches symmetry off. */
+int tc_set_symmetry(tc_ctx* ctx, int nsym, const int32_t* rot, const double* tau);
+
 /* tc_load_orbitals for spin channel `spin` (0 = up, the set of tc_load_orbitals; 1 = down, needs
  * tc_set_nspin(ctx, 2)).  TC mode only: left must be NULL (TC_ERR_UNSUPPORTED otherwise).  occ are the
  * channel's own fillings in [0, 1].  TC_ERR_STATE for spin 1 with one channel; TC_ERR_ARG for another

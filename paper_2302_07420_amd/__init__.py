@@ -69,6 +69,7 @@ def lib():
         "tc_set_options": (I, [P, I, D, I, ctypes.c_uint64]),
         "tc_load_orbitals": (I, [P, I, I, dp, dp, dp]),
         "tc_set_nspin": (I, [P, I]),
+        "tc_set_symmetry": (I, [P, I, ctypes.POINTER(ctypes.c_int32), dp]),
         "tc_load_orbitals_spin": (I, [P, I, I, I, dp, dp, dp]),
         "tc_orbital_energies": (I, [P, dp]),
         "tc_apply": (I, [P, I, dp, dp]),
@@ -161,6 +162,17 @@ class TCOperator:
         """1: both spin channels hold the same orbitals; 2: spin-polarised TC mode (load spin 1 separately)."""
         self._check(self._L.tc_set_nspin(self._h, int(nspin)), "tc_set_nspin")
         self.nspin = int(nspin)
+
+    def set_symmetry(self, ops=None):
+        """Crystal symmetry: ``ops`` a list of (R (3,3) int, tau (3,)) with x -> R (x + tau) on fractional
+        coordinates; None or [] switches it off.  Only the representative k-points' orbitals are used."""
+        if not ops:
+            self._check(self._L.tc_set_symmetry(self._h, 0, None, None), "tc_set_symmetry")
+            return
+        rot = np.ascontiguousarray(np.stack([np.asarray(R, dtype=np.int32) for R, _ in ops]))
+        tau = np.ascontiguousarray(np.stack([np.asarray(t, dtype=np.float64) for _, t in ops]))
+        self._check(self._L.tc_set_symmetry(self._h, len(ops), rot.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                            _dp(tau)), "tc_set_symmetry")
 
     def load_orbitals(self, ik, coeff, occ, left=None, spin=0):
         """Right orbitals ``coeff`` (nband, npw) of k-point ik; ``left`` (same shape) switches that k-point to
@@ -317,9 +329,9 @@ class TCOperator:
 
 
 def from_workload(w, precision=TC_PREC_FP64, terms=TERM_ALL, div_correction=True, device=0, A=None, C=None,
-                  coeff=None, stream=None, batch=0, left=None) -> TCOperator:
+                  coeff=None, stream=None, batch=0, left=None, symmetry=None) -> TCOperator:
     """Build an operator from a ``tcinputs.Workload``: TC mode, or the biorthogonal mode when the workload
-    (or ``left``) holds left orbitals."""
+    (or ``left``) holds left orbitals; ``symmetry``: crystal operations [(R, tau)] (see set_symmetry)."""
     op = TCOperator(device, stream)
     if batch:
         op.set_batch(batch)
@@ -330,6 +342,8 @@ def from_workload(w, precision=TC_PREC_FP64, terms=TERM_ALL, div_correction=True
         op.set_basis(ik, m)
     op.set_jastrow(w.A if A is None else A, w.C if C is None else C)
     op.set_options(precision, w.alpha, div_correction, terms)
+    if symmetry:
+        op.set_symmetry(symmetry)
     cs = w.right if coeff is None else coeff
     ls = w.left if left is None else left
     dn = getattr(w, "right_dn", None)

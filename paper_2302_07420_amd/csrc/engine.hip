@@ -19,10 +19,12 @@
 #include <string>
 #include <thread>
 #include <type_traits>
+#include <unordered_map>
 #include <vector>
 
 #include "../../include/tcmi.h"
 #include "kernels.hpp"
+#include "sym.hpp"
 #include "scf.hpp"
 
 using namespace tcmi;
@@ -166,6 +168,13 @@ struct Problem {
   std::vector<char> loaded_dn;            // per k (nspin = 2)
   double delta_gb = 0, sigma_aux = 0;
   int batch = 0;                          // targets per batch (0 = automatic)
+  // crystal symmetry (tc_set_symmetry): operations x -> R (x + tau) and the k-point orbits
+  int nsym = 0;
+  std::vector<int> symR;                  // [nsym][9]
+  std::vector<double> symT;               // [nsym][3]
+  std::vector<int> krep, kop, kb;         // per k: representative, operation (-1: itself), b [3]
+  std::vector<int> irr;                   // representative k-points, increasing
+  bool sym_ready = false;                 // the other k-points' orbitals generated since the last load
 
   int P() const { return nk * nb; }
   long NR() const { return long(N) * N * N; }
@@ -258,6 +267,12 @@ struct Shared {                       // precision-independent device data
   DBuf<double> eps;                   // [P] complex orbital energies
   // target-set side of the corrections (tc_apply)
   DBuf<double> ZgT, WgT, dhc2T, dhc3T, ST, OT, ecorrT;
+  // symmetry expansion: per-k operation data, representatives, coefficient maps, and the outputs and
+  // energy slots of the representatives' orbitals
+  DBuf<SymK> symk;
+  DBuf<int> irrk, symg0;                // [nirr], [nk][npw_max]
+  DBuf<double> symph;                   // [nk][npw_max] complex phases
+  DBuf<double> outI, epartI;            // [nirr nb][npw_max] complex, [nirr nb][kAccSlots]
 };
 
 // ------------------------------------------------------------------ FP64 helper kernels
@@ -739,6 +754,7 @@ struct Engine {
   virtual void upload_tables(const Problem& pb, const TableVariant& tv) = 0;
   virtual void apply(hipStream_t s, Shared& sh, const Problem& pb, double* stage_ms,
                      const TargetSet* ts = nullptr) = 0;
+  virtual void apply_sym(hipStream_t s, Shared& sh, const Problem& pb, double* stage_ms) = 0;
   Prof* prof = nullptr;
 };
 
@@ -810,6 +826,8 @@ struct EngineT : Engine {
   int nspin_alloc = 1;
   // target set of tc_apply (trial vectors)
   DBuf<cx<R>> psiT, DT;              // [NT][NR], [3][NT][NR]
+  DBuf<cx<R>> H3I;                   // [nirr nb][3][NR]  H3a4 of the representatives' orbitals
+  DBuf<R> h5I;                       // [nirr nb][NR]
   DBuf<cx<double>> psiT64, prodT;    // [NT][NR], [2][NT][NR]
   int S = 1;
   // kernel tables (scaled by 1/(Omega N^3))
@@ -1364,6 +1382,253 @@ struct EngineT : Engine {
       msB += b;
     }
     for (auto e : bev) (void)hipEventDestroy(e);
+    stage_ms[0] = ev.ms(0, 1);
+    stage_ms[1] = ev.ms(1, 2);
+    stage_ms[2] = ev.ms(2, 3);
+    stage_ms[3] = msA;
+    stage_ms[4] = msB;
+    stage_ms[5] = ev.ms(3, 5) - msA - msB;
+  }
+
+  // Application with crystal symmetry (TC mode, one spin channel): the occupied-occupied rows (q2 of
+  // Algs. 3a2, 3a4, 3b2) and the targets are the orbitals of the representative k-points only.  h5 and
+  // H3a4 of the other orbitals follow from the representatives' by the grid permutation of their
+  // operation (k_sym_fields); the outputs and energy slots of the other orbitals from the
+  // representatives' (k_sym_coef, k_sym_epart).  Densities, partner sums and corrections use every
+  // orbital.
+  void apply_sym(hipStream_t s, Shared& sh, const Problem& pb, double* stage_ms) override {
+    const int P = pb.P();
+    const int nb = pb.nb;
+    const int npm = pb.npw_max;
+    const int nirr = int(pb.irr.size());
+    const int PI = nirr * nb;
+    const Masks m = make_masks(pb.mask);
+    ensure(pb, size_t(8) << 30);
+    const MeshInfo mi{pb.n1, pb.n2, pb.n3, nb, P, nb, sh.irrk.p};   // rows / targets: representatives
+    Recip rc;
+    for (int i = 0; i < 9; ++i) rc.b[i] = pb.B[i];
+    Basis<R> bm, mm;
+    for (int i = 0; i < 9; ++i) bm.b[i] = R(pb.B[i]);
+    for (int d = 0; d < 3; ++d)
+      for (int e = 0; e < 3; ++e)
+        mm.b[3 * d + e] = R(pb.B[3 * d] * pb.B[3 * e] + pb.B[3 * d + 1] * pb.B[3 * e + 1] + pb.B[3 * d + 2] * pb.B[3 * e + 2]);
+    const Tables tb{tV.p, tU1.p, tU2.p, dfr.p};
+    const double fb = double(sizeof(cx<R>)) * NR;
+    const double fd = double(sizeof(cx<double>)) * NR;
+    const double tabB = 3.0 * double(sizeof(R)) * NR * double((2 * pb.n1 - 1) * (2 * pb.n2 - 1) * (2 * pb.n3 - 1));
+    Prof* pf = prof;
+    auto K = [&](int id, double bytes, auto&& launch) {
+      ProfScope ps(pf, s, id, bytes);
+      launch();
+    };
+    psiT.alloc(size_t(PI) * NR);
+    DT.alloc(size_t(3) * PI * NR);
+    H3I.alloc(size_t(3) * PI * NR);
+    h5I.alloc(size_t(PI) * NR);
+    sh.outI.alloc(size_t(2) * PI * npm);
+    sh.epartI.alloc(size_t(kAccSlots) * PI);
+    Events ev(6);
+    double msA = 0, msB = 0;
+    TC_HIP(hipEventRecord(ev.e[0], s));
+
+    // ---- 0: G -> r of every orbital; the representatives' fields as targets
+    TC_HIP(hipMemsetAsync(psi.p, 0, size_t(P) * NR * sizeof(cx<R>), s));
+    TC_HIP(hipMemsetAsync(D.p, 0, size_t(3) * P * NR * sizeof(cx<R>), s));
+    const unsigned gsc = nblk(long(P) * npm);
+    K(TC_K_SCATTER, 0.0, [&] {
+      hipLaunchKernelGGL((k_scatter<R>), dim3(gsc), dim3(256), 0, s, sh.coef.p, sh.boxidx.p, sh.npw.p, sh.kg.p, nb,
+                         npm, P, -1, psi.p, NR);
+      for (int c = 0; c < 3; ++c)
+        hipLaunchKernelGGL((k_scatter<R>), dim3(gsc), dim3(256), 0, s, sh.coef.p, sh.boxidx.p, sh.npw.p, sh.kg.p, nb,
+                           npm, P, c, D.p + size_t(c) * P * NR, NR);
+    });
+    fft3d_t<R, N>(psi.p, P, +1, s, pf);
+    fft3d_t<R, N>(D.p, 3L * P, +1, s, pf);
+    for (int i = 0; i < nirr; ++i) {
+      const size_t blk = size_t(nb) * NR, src = size_t(pb.irr[i]) * blk, dst = size_t(i) * blk;
+      TC_HIP(hipMemcpyAsync(psiT.p + dst, psi.p + src, blk * sizeof(cx<R>), hipMemcpyDeviceToDevice, s));
+      for (int c = 0; c < 3; ++c)
+        TC_HIP(hipMemcpyAsync(DT.p + size_t(c) * PI * NR + dst, D.p + size_t(c) * P * NR + src, blk * sizeof(cx<R>),
+                              hipMemcpyDeviceToDevice, s));
+    }
+    K(TC_K_OTHER, 6.0 * fb * P, [&] {
+      hipLaunchKernelGGL((k_lattice3<R, N>), dim3(nblk(long(P) * NR)), dim3(256), 0, s, D.p, Dl.p, bm, long(P), NR,
+                         long(P) * NR);
+    });
+    TC_HIP(hipEventRecord(ev.e[1], s));
+
+    // ---- 1: densities and Hartree-type fields (every orbital)
+    TC_HIP(hipMemsetAsync(loc.p, 0, 8 * NR * sizeof(cx<R>), s));
+    K(TC_K_OTHER, fb * (4.0 * P + 4.0), [&] {
+      hipLaunchKernelGGL((k_density<R, N>), dim3(nblk(NR)), dim3(256), 0, s, psi.p, psi.p, D.p, sh.w.p, P, nJ.p,
+                         nJ.p + NR);
+    });
+    TC_HIP(hipMemcpyAsync(wk.p, nJ.p, 4 * NR * sizeof(cx<R>), hipMemcpyDeviceToDevice, s));
+    fft3d_t<R, N>(wk.p, 4, -1, s, pf);
+    K(TC_K_OTHER, fb * 9.0, [&] {
+      hipLaunchKernelGGL((k_hartree_g<R, N>), dim3(nblk(NR)), dim3(256), 0, s, rc, tHV.p, tHU.p, wk.p, wk.p + NR,
+                         wk.p + 4 * NR);
+    });
+    fft3d_t<R, N>(wk.p + 4 * NR, 5, +1, s, pf);
+    TC_HIP(hipMemcpyAsync(loc.p, wk.p + 4 * NR, 5 * NR * sizeof(cx<R>), hipMemcpyDeviceToDevice, s));
+    K(TC_K_OTHER, fb * 7.0, [&] {
+      hipLaunchKernelGGL((k_mul_vec_scalar<R, N>), dim3(nblk(NR)), dim3(256), 0, s, loc.p + NR, nJ.p, wk.p);
+    });
+    fft3d_t<R, N>(wk.p, 3, -1, s, pf);
+    K(TC_K_OTHER, fb * 4.0, [&] {
+      hipLaunchKernelGGL((k_gdiv<R, N>), dim3(nblk(NR)), dim3(256), 0, s, rc, tHU.p, wk.p, wk.p + 3 * NR);
+    });
+    fft3d_t<R, N>(wk.p + 3 * NR, 1, +1, s, pf);
+    TC_HIP(hipMemcpyAsync(loc.p + 5 * NR, wk.p + 3 * NR, NR * sizeof(cx<R>), hipMemcpyDeviceToDevice, s));
+    TC_HIP(hipEventRecord(ev.e[2], s));
+
+    // ---- 2: occupied-occupied pass with the representatives' orbitals as rows, then the images
+    const bool need_occ = m.m3a2 || m.m3a4 || m.m3b2 || m.m3b5;
+    const int chunk = (P + S - 1) / S;
+    TC_HIP(hipMemsetAsync(H3a4.p, 0, size_t(3) * P * NR * sizeof(cx<R>), s));
+    TC_HIP(hipMemsetAsync(h5.p, 0, size_t(P) * NR * sizeof(R), s));
+    if (need_occ) {
+      for (int a0 = 0; a0 < PI; a0 += T) {
+        const int nt = std::min(T, PI - a0);
+        const long npair = long(nt) * P;
+        const FusedArgs fa{P, nt, a0, S, chunk};
+        K(TC_K_XY_PAIR_OCC, fb * (npair + nt + P), [&] {
+          hipLaunchKernelGGL((k_pair_xy<R, N, true>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, psiT.p, psi.p, fa,
+                             bufA.p);
+        });
+        K(TC_K_ZCONV_OCC, fb * 5.0 * npair + tabB, [&] {
+          zconv<OP_O>(s, npair, a0, mi, tb, 0);
+        });
+        K(TC_K_FUSED_O, fb * (4.0 * npair + P) + 3.5 * fb * nt * S, [&] {
+          hipLaunchKernelGGL((k_fused_O<R, N>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, bufB.p, psi.p, sh.w.p,
+                             fa, mi, rc, dfr.p, h5part.p, H3part.p);
+        });
+        K(TC_K_SUM_PARTS, 4.0 * fb * nt * (S + 1), [&] {
+          hipLaunchKernelGGL((k_sum_parts<R, N>), dim3(nblk(long(nt) * NR)), dim3(256), 0, s, 0, S, nt, a0, 0,
+                             h5part.p, H3part.p, nullptr, nullptr, h5I.p, H3I.p, nullptr, nullptr);
+        });
+      }
+      K(TC_K_OTHER, fb * 4.0 * (P + PI), [&] {
+        hipLaunchKernelGGL((k_sym_fields<R, N>), dim3(nblk(long(P) * NR)), dim3(256), 0, s, sh.symk.p, nb, P, h5I.p,
+                           H3I.p, h5.p, H3a4.p);
+      });
+      K(TC_K_OTHER, fb * (5.0 * P + 4.0), [&] {
+        hipLaunchKernelGGL((k_reduce_occ<R, N, R>), dim3(nblk(NR)), dim3(256), 0, s, h5.p, H3a4.p, psi.p, sh.w.p, P,
+                           loc.p + 6 * NR, wk.p);
+      });
+      fft3d_t<R, N>(wk.p, 3, -1, s, pf);
+      K(TC_K_OTHER, fb * 4.0, [&] {
+        hipLaunchKernelGGL((k_gdiv<R, N>), dim3(nblk(NR)), dim3(256), 0, s, rc, tHU.p, wk.p, wk.p + 3 * NR);
+      });
+      fft3d_t<R, N>(wk.p + 3 * NR, 1, +1, s, pf);
+      TC_HIP(hipMemcpyAsync(loc.p + 7 * NR, wk.p + 3 * NR, NR * sizeof(cx<R>), hipMemcpyDeviceToDevice, s));
+    }
+    K(TC_K_OTHER, 6.0 * fb * P, [&] {
+      hipLaunchKernelGGL((k_lattice3<R, N>), dim3(nblk(long(P) * NR)), dim3(256), 0, s, H3a4.p, Hl.p, bm, long(P),
+                         3 * NR, NR);
+    });
+    TC_HIP(hipEventRecord(ev.e[3], s));
+
+    // ---- 3/4: the representatives' orbitals as targets (partners: every orbital)
+    const bool need_A = m.m2ax || m.m2bx1 || m.m2bx2 || m.m3a3 || m.m3a4 || m.m3b4 || m.m3b6;
+    const bool need_B = m.m2bx2 || m.m3b3 || m.m3b4 || m.m3b5;
+    for (int t0 = 0; t0 < PI; t0 += T) {
+      const int nt = std::min(T, PI - t0);
+      const long npair = long(nt) * P;
+      TC_HIP(hipMemsetAsync(acc.p, 0, size_t(kAccSlots) * T * NR * sizeof(cx<double>), s));
+      TC_HIP(hipMemsetAsync(h4.p, 0, size_t(3) * T * NR * sizeof(cx<R>), s));
+      Events bev(3);
+      TC_HIP(hipEventRecord(bev.e[0], s));
+      const double part = fb * nt * S;
+      if (need_A) {
+        const FusedArgs fa{P, nt, t0, S, chunk};
+        K(TC_K_XY_PAIR_TGT, fb * (npair + nt + P), [&] {
+          hipLaunchKernelGGL((k_pair_xy<R, N, false>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, psi.p, psiT.p, fa,
+                             bufA.p);
+        });
+        K(TC_K_ZCONV_A1, fb * 6.0 * npair + tabB, [&] {
+          zconv<OP_A1>(s, npair, t0, mi, tb, 1);
+        });
+        K(TC_K_FUSED_A, fb * ((m.m3b6 ? 9.0 : 5.0) * npair + 8.0 * P + nt) + 6.0 * part, [&] {
+          hipLaunchKernelGGL((k_fused_A<R, N>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, bufB.p, psi.p, Dl.p, Hl.p,
+                             nJ.p, sh.w.p, fa, m, int(m.m3b6 != 0), mi, bm, mm, dfr.p, bufA.p, gpart.p, h4part.p);
+        });
+        K(TC_K_SUM_PARTS, 6.0 * part + 6.0 * fd * nt + 3.0 * fb * nt, [&] {
+          hipLaunchKernelGGL((k_sum_parts<R, N>), dim3(nblk(long(nt) * NR)), dim3(256), 0, s, 1, S, nt, t0, 0, nullptr,
+                             nullptr, gpart.p, h4part.p, nullptr, nullptr, acc.p, h4.p);
+        });
+        if (m.m3b6) {
+          K(TC_K_ZCONV_A2, fb * 5.0 * npair + tabB, [&] {
+            zconv<OP_A2>(s, npair, t0, mi, tb, 1);
+          });
+          K(TC_K_FUSED_Y, fb * (npair + P) + part, [&] {
+            hipLaunchKernelGGL((k_fused_Y<R, N>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, bufB.p, psi.p, sh.w.p,
+                               fa, 1.0, gpart.p);
+          });
+          K(TC_K_SUM_PARTS, part + 2.0 * fd * nt, [&] {
+            hipLaunchKernelGGL((k_sum_parts<R, N>), dim3(nblk(long(nt) * NR)), dim3(256), 0, s, 2, S, nt, t0, 2,
+                               nullptr, nullptr, gpart.p, nullptr, nullptr, nullptr, acc.p, nullptr);
+          });
+        }
+      }
+      TC_HIP(hipEventRecord(bev.e[1], s));
+      if (need_B) {
+        const FusedArgs fy{P, nt, t0, S, chunk};
+        K(TC_K_OTHER, fb * 13.0 * nt, [&] {
+          hipLaunchKernelGGL((k_passB_Z<R, N>), dim3(nblk(long(nt) * NR)), dim3(256), 0, s, psiT.p, DT.p, loc.p + NR,
+                             h4.p, t0, nt, PI, m, bm, Z.p);
+        });
+        K(TC_K_XY_PASSB, fb * (2.0 * npair + 4.0 * P + 4.0 * nt), [&] {
+          hipLaunchKernelGGL((k_passB_xy<R, N>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, psiT.p, psi.p, Z.p, Hl.p,
+                             fy, mi, dfr.p, R(m.m3b5), bufA.p);
+        });
+        K(TC_K_ZCONV_B, fb * 3.0 * npair + tabB, [&] {
+          zconv<OP_B>(s, npair, t0, mi, tb, 1);
+        });
+        K(TC_K_FUSED_Y, fb * (npair + P) + part, [&] {
+          hipLaunchKernelGGL((k_fused_Y<R, N>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, bufB.p, psi.p, sh.w.p,
+                             fy, 1.0, gpart.p);
+        });
+        K(TC_K_SUM_PARTS, part + 2.0 * fd * nt, [&] {
+          hipLaunchKernelGGL((k_sum_parts<R, N>), dim3(nblk(long(nt) * NR)), dim3(256), 0, s, 2, S, nt, t0, 3, nullptr,
+                             nullptr, gpart.p, nullptr, nullptr, nullptr, acc.p, nullptr);
+        });
+      }
+      TC_HIP(hipEventRecord(bev.e[2], s));
+      K(TC_K_OTHER, fb * 16.0 * nt + 8.0 * fd * nt, [&] {
+        hipLaunchKernelGGL((k_local<R, N>), dim3(nblk(long(nt) * NR)), dim3(256), 0, s, psiT.p, DT.p, loc.p, h4.p, t0,
+                           nt, PI, m, acc.p, g.p);
+        hipLaunchKernelGGL((k_epart<R, N>), dim3(kAccSlots * nt), dim3(256), 0, s, psiT.p, acc.p, t0, nt,
+                           sh.epartI.p);
+      });
+      fft3d_t<R, N>(g.p, nt, -1, s, pf);
+      K(TC_K_OTHER, 0.0, [&] {
+        hipLaunchKernelGGL((k_gather<R>), dim3(nblk(long(nt) * npm)), dim3(256), 0, s, g.p, sh.boxidx.p, sh.npw.p, nb,
+                           npm, t0, nt, 1.0 / double(NR), sh.outI.p, NR, sh.irrk.p);
+      });
+      TC_HIP(hipEventSynchronize(bev.e[2]));
+      msA += bev.ms(0, 1);
+      msB += bev.ms(1, 2);
+    }
+    // every orbital's output and energy slots from its representative's
+    K(TC_K_OTHER, 0.0, [&] {
+      hipLaunchKernelGGL(k_sym_coef, dim3(nblk(long(P) * npm)), dim3(256), 0, s, sh.symk.p, sh.symg0.p, sh.symph.p,
+                         sh.npw.p, pb.nk, nb, npm, sh.outI.p, sh.out.p);
+      hipLaunchKernelGGL(k_sym_epart, dim3(nblk(long(P) * kAccSlots)), dim3(256), 0, s, sh.symk.p, nb, P, kAccSlots,
+                         sh.epartI.p, sh.epart.p);
+    });
+    TC_HIP(hipEventRecord(ev.e[4], s));
+
+    // ---- 5: kinetic energy and FP64 corrections (every orbital)
+    K(TC_K_CORR, 0.0, [&] {
+      hipLaunchKernelGGL(k_kinetic, dim3(P), dim3(256), 0, s, sh.coef.p, sh.coef.p, sh.kg.p, sh.npw.p, nb, npm,
+                         sh.tkin.p);
+      TC_HIP(hipMemsetAsync(sh.ecorr.p, 0, size_t(2) * P * sizeof(double), s));
+      if (pb.div && (pb.mask & TC_T_CORR) && (m.m2ax || m.m3a2 || m.m3b6)) corrections(s, sh, pb, m, nullptr);
+    });
+    TC_HIP(hipEventRecord(ev.e[5], s));
+    TC_HIP(hipEventSynchronize(ev.e[5]));
+    if (pf && pf->on) pf->collect();
     stage_ms[0] = ev.ms(0, 1);
     stage_ms[1] = ev.ms(1, 2);
     stage_ms[2] = ev.ms(2, 3);
@@ -1928,6 +2193,300 @@ int guard(tc_ctx* c, F&& f) {
 
 bool grid_supported(int N) { return N == 8 || N == 12 || N == 16 || N == 24 || N == 32 || N == 48; }
 
+void upload_basis_data(tc_ctx* c);
+
+// ------------------------------------------------------------------ crystal symmetry (host)
+// Integer inverse of a unimodular 3x3 matrix (row-major).
+void int_inverse3(const int* R, int* Ri) {
+  const int det = R[0] * (R[4] * R[8] - R[5] * R[7]) - R[1] * (R[3] * R[8] - R[5] * R[6]) +
+                  R[2] * (R[3] * R[7] - R[4] * R[6]);
+  const int adj[9] = {R[4] * R[8] - R[5] * R[7], R[2] * R[7] - R[1] * R[8], R[1] * R[5] - R[2] * R[4],
+                      R[5] * R[6] - R[3] * R[8], R[0] * R[8] - R[2] * R[6], R[2] * R[3] - R[0] * R[5],
+                      R[3] * R[7] - R[4] * R[6], R[1] * R[6] - R[0] * R[7], R[0] * R[4] - R[1] * R[3]};
+  for (int i = 0; i < 9; ++i) Ri[i] = adj[i] / det;
+}
+
+// The image under operation o of mesh k-point k: index of R^T k (mod 1) and b = R^T k - k'
+// (fractional units); false when R^T k is off the mesh.
+bool sym_map_k(const Problem& pb, const int* R, int k, int* kout, int* b) {
+  double f[3], g[3];
+  pb.kfrac(k, f);
+  const int n[3] = {pb.n1, pb.n2, pb.n3};
+  int idx[3];
+  for (int i = 0; i < 3; ++i) {
+    g[i] = R[i] * f[0] + R[3 + i] * f[1] + R[6 + i] * f[2];   // (R^T f)_i
+    const double x = g[i] * n[i];
+    const double xr = std::round(x);
+    if (std::fabs(x - xr) > 1e-9) return false;
+    const int t = int(xr);
+    idx[i] = ((t % n[i]) + n[i]) % n[i];
+    b[i] = (t - idx[i]) / n[i];
+  }
+  *kout = (idx[0] * pb.n2 + idx[1]) * pb.n3 + idx[2];
+  return true;
+}
+
+int set_symmetry(tc_ctx* c, int nsym, const int32_t* rot, const double* tau) {
+  Problem& pb = c->pb;
+  if (!pb.cell || pb.nk == 0 || pb.N == 0) return fail(c, TC_ERR_STATE, "set the cell, k-mesh and grid first");
+  if (nsym < 0) return fail(c, TC_ERR_ARG, "nsym must be >= 0");
+  pb.nsym = 0;
+  pb.sym_ready = false;
+  c->have_result = false;
+  if (nsym == 0) return TC_OK;
+  if (!rot || !tau) return fail(c, TC_ERR_ARG, "null operations");
+  // lattice L (rows a_i) and its inverse
+  const double* L = pb.lat;
+  double Li[9];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) Li[3 * i + j] = pb.B[3 * j + i] / (2 * kPi);   // L^-1 = B^T / 2 pi
+  for (int o = 0; o < nsym; ++o) {
+    const int* R = rot + 9 * o;
+    const int det = R[0] * (R[4] * R[8] - R[5] * R[7]) - R[1] * (R[3] * R[8] - R[5] * R[6]) +
+                    R[2] * (R[3] * R[7] - R[4] * R[6]);
+    if (det != 1 && det != -1) return fail(c, TC_ERR_ARG, "operation " + std::to_string(o) + ": det R must be +-1");
+    // S = L^T R L^-T must be orthogonal
+    double S[9];
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) {
+        double v = 0;
+        for (int a = 0; a < 3; ++a)
+          for (int b = 0; b < 3; ++b) v += L[3 * a + i] * R[3 * a + b] * Li[3 * j + b];
+        S[3 * i + j] = v;
+      }
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) {
+        double v = 0;
+        for (int a = 0; a < 3; ++a) v += S[3 * i + a] * S[3 * j + a];
+        if (std::fabs(v - (i == j ? 1.0 : 0.0)) > 1e-9)
+          return fail(c, TC_ERR_ARG, "operation " + std::to_string(o) + " is not an isometry of the lattice");
+      }
+    for (int i = 0; i < 3; ++i) {
+      const double x = tau[3 * o + i] * pb.N;
+      if (std::fabs(x - std::round(x)) > 1e-9)
+        return fail(c, TC_ERR_ARG, "operation " + std::to_string(o) + ": N tau must be integer (grid-preserving)");
+    }
+    for (int k = 0; k < pb.nk; ++k) {
+      int kk, b[3];
+      if (!sym_map_k(pb, R, k, &kk, b))
+        return fail(c, TC_ERR_ARG, "operation " + std::to_string(o) + " does not map the k-mesh onto itself");
+    }
+  }
+  // closure: {R1|tau1}{R2|tau2} = x -> R1 R2 x + R1 R2 tau2 + R1 tau1 must be in the set (mod lattice)
+  auto wvec = [&](const int* R, const double* t, double* w) {
+    for (int i = 0; i < 3; ++i) w[i] = R[3 * i] * t[0] + R[3 * i + 1] * t[1] + R[3 * i + 2] * t[2];
+  };
+  auto same_mod1 = [](const double* a, const double* b) {
+    for (int i = 0; i < 3; ++i) {
+      const double d = a[i] - b[i];
+      if (std::fabs(d - std::round(d)) > 1e-9) return false;
+    }
+    return true;
+  };
+  for (int o1 = 0; o1 < nsym; ++o1)
+    for (int o2 = 0; o2 < nsym; ++o2) {
+      const int *R1 = rot + 9 * o1, *R2 = rot + 9 * o2;
+      int A[9];
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) A[3 * i + j] = R1[3 * i] * R2[j] + R1[3 * i + 1] * R2[3 + j] + R1[3 * i + 2] * R2[6 + j];
+      double w2[3], w[3], w1[3];
+      wvec(A, tau + 3 * o2, w2);
+      wvec(R1, tau + 3 * o1, w1);
+      for (int i = 0; i < 3; ++i) w[i] = w2[i] + w1[i];
+      bool found = false;
+      for (int o = 0; o < nsym && !found; ++o) {
+        if (!std::equal(A, A + 9, rot + 9 * o)) continue;
+        double wo[3];
+        wvec(rot + 9 * o, tau + 3 * o, wo);
+        found = same_mod1(w, wo);
+      }
+      if (!found) return fail(c, TC_ERR_ARG, "the operations do not form a group");
+    }
+  pb.symR.assign(rot, rot + 9 * nsym);
+  pb.symT.assign(tau, tau + 3 * nsym);
+  // orbits: the representative is the lowest k index of its orbit
+  pb.krep.assign(pb.nk, -1);
+  pb.kop.assign(pb.nk, -1);
+  pb.kb.assign(3 * size_t(pb.nk), 0);
+  pb.irr.clear();
+  for (int k = 0; k < pb.nk; ++k) {
+    if (pb.krep[k] >= 0) continue;
+    pb.krep[k] = k;
+    pb.irr.push_back(k);
+    for (int o = 0; o < nsym; ++o) {
+      int kk, b[3];
+      sym_map_k(pb, rot + 9 * o, k, &kk, b);
+      if (pb.krep[kk] >= 0) continue;
+      pb.krep[kk] = k;
+      pb.kop[kk] = o;
+      for (int i = 0; i < 3; ++i) pb.kb[3 * kk + i] = b[i];
+    }
+  }
+  pb.nsym = nsym;
+  return TC_OK;
+}
+
+// Before the first application after a load: generates the orbitals (and fillings) of every
+// non-representative k-point from its representative's, checks that each representative's weighted
+// occupied set is invariant under its little group (the condition under which the fields of the images
+// equal the directly computed ones), and uploads the expansion tables of sym.hpp.
+int sym_prepare(tc_ctx* c) {
+  Problem& pb = c->pb;
+  Shared& sh = c->sh;
+  const int nk = pb.nk, nb = pb.nb, npm = pb.npw_max, N = pb.N;
+  const double* L = pb.lat;
+  double Li[9];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) Li[3 * i + j] = pb.B[3 * j + i] / (2 * kPi);
+  std::vector<double> cf(size_t(2) * pb.P() * npm);
+  TC_HIP(hipMemcpy(cf.data(), sh.coef.p, cf.size() * sizeof(double), hipMemcpyDeviceToHost));
+  auto key = [](int a, int b, int d) { return ((long long)(a + 1024) << 22) | ((long long)(b + 1024) << 11) | (d + 1024); };
+  // plane-wave lookup of each representative
+  std::vector<std::unordered_map<long long, int>> look(nk);
+  for (int r : pb.irr)
+    for (int g = 0; g < pb.npw[r]; ++g) {
+      const int* m = &pb.miller[r][3 * g];
+      look[r][key(m[0], m[1], m[2])] = g;
+    }
+  // map of operation o with shift b from representative r onto a plane-wave list (miller, n):
+  // g0[g] and the phase e^{2 pi i (m - b).tau}
+  auto build_map = [&](int r, int o, const int* b, const std::vector<int>& mil, int n, int* g0, double* ph) -> bool {
+    int Ri[9];
+    int_inverse3(&pb.symR[9 * o], Ri);
+    const double* t = &pb.symT[3 * o];
+    for (int g = 0; g < n; ++g) {
+      const int mb[3] = {mil[3 * g] - b[0], mil[3 * g + 1] - b[1], mil[3 * g + 2] - b[2]};
+      int m0[3];
+      for (int i = 0; i < 3; ++i) m0[i] = Ri[i] * mb[0] + Ri[3 + i] * mb[1] + Ri[6 + i] * mb[2];   // R^-T (m - b)
+      auto it = look[r].find(key(m0[0], m0[1], m0[2]));
+      if (it == look[r].end()) return false;
+      g0[g] = it->second;
+      const double phase = 2 * kPi * (mb[0] * t[0] + mb[1] * t[1] + mb[2] * t[2]);
+      ph[2 * g] = std::cos(phase);
+      ph[2 * g + 1] = std::sin(phase);
+    }
+    return true;
+  };
+  // little-group invariance of each representative's weighted occupied set
+  for (int r : pb.irr) {
+    const int n = pb.npw[r];
+    std::vector<int> g0(n);
+    std::vector<double> ph(2 * size_t(n));
+    for (int o = 0; o < pb.nsym; ++o) {
+      int kk, b[3];
+      sym_map_k(pb, &pb.symR[9 * o], r, &kk, b);
+      if (kk != r) continue;
+      if (!build_map(r, o, b, pb.miller[r], n, g0.data(), ph.data()))
+        return fail(c, TC_ERR_ARG, "plane waves of k-point " + std::to_string(r) + " are not invariant under its little group");
+      // M[mu][nu] = <c_mu | O c_nu>; needs M M^H = 1 and M F = F M (F = fillings)
+      std::vector<double> M(2 * size_t(nb) * nb, 0.0);
+      for (int mu = 0; mu < nb; ++mu)
+        for (int nu = 0; nu < nb; ++nu) {
+          const double* x = &cf[2 * (size_t(r * nb + mu) * npm)];
+          const double* y = &cf[2 * (size_t(r * nb + nu) * npm)];
+          double sr = 0, si = 0;
+          for (int g = 0; g < n; ++g) {
+            const double yr = ph[2 * g] * y[2 * g0[g]] - ph[2 * g + 1] * y[2 * g0[g] + 1];
+            const double yi = ph[2 * g] * y[2 * g0[g] + 1] + ph[2 * g + 1] * y[2 * g0[g]];
+            sr += x[2 * g] * yr + x[2 * g + 1] * yi;
+            si += x[2 * g] * yi - x[2 * g + 1] * yr;
+          }
+          M[2 * (mu * nb + nu)] = sr;
+          M[2 * (mu * nb + nu) + 1] = si;
+        }
+      double err = 0;
+      for (int i = 0; i < nb; ++i)
+        for (int j = 0; j < nb; ++j) {
+          double ur = 0, ui = 0;
+          for (int l = 0; l < nb; ++l) {
+            const double ar = M[2 * (i * nb + l)], ai = M[2 * (i * nb + l) + 1];
+            const double br = M[2 * (j * nb + l)], bi = -M[2 * (j * nb + l) + 1];
+            ur += ar * br - ai * bi;
+            ui += ar * bi + ai * br;
+          }
+          err = std::max(err, std::hypot(ur - (i == j ? 1.0 : 0.0), ui));
+          const double fi = pb.occ[size_t(r) * nb + i], fj = pb.occ[size_t(r) * nb + j];
+          err = std::max(err, std::hypot(M[2 * (i * nb + j)], M[2 * (i * nb + j) + 1]) * std::fabs(fi - fj));
+        }
+      if (err > 1e-8)
+        return fail(c, TC_ERR_ARG, "the occupied orbitals of k-point " + std::to_string(r) +
+                                       " are not invariant under its little group (deviation " + std::to_string(err) + ")");
+    }
+  }
+  // generation of the other k-points and the expansion tables
+  std::vector<int> g0(size_t(nk) * npm, 0);
+  std::vector<double> ph(size_t(2) * nk * npm, 0.0);
+  std::vector<SymK> sk(nk);
+  std::vector<int> rix(nk, -1);
+  for (size_t i = 0; i < pb.irr.size(); ++i) rix[pb.irr[i]] = int(i);
+  for (int k = 0; k < nk; ++k) {
+    const int r = pb.krep[k], o = pb.kop[k];
+    SymK& x = sk[k];
+    x.rk = rix[r];
+    if (o < 0) {
+      for (int i = 0; i < 9; ++i) {
+        x.R[i] = (i % 4 == 0);
+        x.St[i] = (i % 4 == 0) ? 1.0 : 0.0;
+      }
+      for (int i = 0; i < 3; ++i) x.v[i] = x.b[i] = 0;
+      for (int g = 0; g < pb.npw[k]; ++g) {
+        g0[size_t(k) * npm + g] = g;
+        ph[2 * (size_t(k) * npm + g)] = 1.0;
+      }
+      continue;
+    }
+    const int* R = &pb.symR[9 * o];
+    const double* t = &pb.symT[3 * o];
+    for (int i = 0; i < 9; ++i) x.R[i] = R[i];
+    for (int i = 0; i < 3; ++i) {
+      const double v = R[3 * i] * t[0] + R[3 * i + 1] * t[1] + R[3 * i + 2] * t[2];
+      x.v[i] = int(std::lround(v * N));
+      x.b[i] = pb.kb[3 * k + i];
+    }
+    // S^T = L^-1 R^T L (Cartesian)
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) {
+        double v = 0;
+        for (int a = 0; a < 3; ++a)
+          for (int b = 0; b < 3; ++b) v += Li[3 * i + a] * R[3 * b + a] * L[3 * b + j];
+        x.St[3 * i + j] = v;
+      }
+    if (pb.npw[k] != pb.npw[r] ||
+        !build_map(r, o, x.b, pb.miller[k], pb.npw[k], &g0[size_t(k) * npm], &ph[2 * size_t(k) * npm]))
+      return fail(c, TC_ERR_ARG, "plane waves of k-point " + std::to_string(k) +
+                                     " are not the image of those of k-point " + std::to_string(r));
+    for (int mu = 0; mu < nb; ++mu) {
+      double* dst = &cf[2 * (size_t(k * nb + mu) * npm)];
+      const double* src = &cf[2 * (size_t(r * nb + mu) * npm)];
+      for (int g = 0; g < npm; ++g) {
+        double re = 0, im = 0;
+        if (g < pb.npw[k]) {
+          const int s0 = g0[size_t(k) * npm + g];
+          const double pr = ph[2 * (size_t(k) * npm + g)], pi = ph[2 * (size_t(k) * npm + g) + 1];
+          re = pr * src[2 * s0] - pi * src[2 * s0 + 1];
+          im = pr * src[2 * s0 + 1] + pi * src[2 * s0];
+        }
+        dst[2 * g] = re;
+        dst[2 * g + 1] = im;
+      }
+      pb.occ[size_t(k) * nb + mu] = pb.occ[size_t(r) * nb + mu];
+    }
+    pb.loaded[k] = 1;
+  }
+  TC_HIP(hipMemcpy(sh.coef.p, cf.data(), cf.size() * sizeof(double), hipMemcpyHostToDevice));
+  upload_basis_data(c);
+  sh.symk.alloc(nk);
+  sh.irrk.alloc(pb.irr.size());
+  sh.symg0.alloc(g0.size());
+  sh.symph.alloc(ph.size());
+  TC_HIP(hipMemcpy(sh.symk.p, sk.data(), sk.size() * sizeof(SymK), hipMemcpyHostToDevice));
+  TC_HIP(hipMemcpy(sh.irrk.p, pb.irr.data(), pb.irr.size() * sizeof(int), hipMemcpyHostToDevice));
+  TC_HIP(hipMemcpy(sh.symg0.p, g0.data(), g0.size() * sizeof(int), hipMemcpyHostToDevice));
+  TC_HIP(hipMemcpy(sh.symph.p, ph.data(), ph.size() * sizeof(double), hipMemcpyHostToDevice));
+  pb.sym_ready = true;
+  return TC_OK;
+}
+
 int prepare(tc_ctx* c) {
   Problem& pb = c->pb;
   if (!pb.cell) return fail(c, TC_ERR_STATE, "tc_set_cell not called");
@@ -1937,9 +2496,13 @@ int prepare(tc_ctx* c) {
   if (pb.nb == 0) return fail(c, TC_ERR_STATE, "no orbitals loaded");
   int nleft = 0;
   for (int k = 0; k < pb.nk; ++k) {
-    if (!pb.loaded[k]) return fail(c, TC_ERR_STATE, "orbitals of k-point " + std::to_string(k) + " not loaded");
+    // with symmetry, the orbitals of k-points other than the representatives are generated
+    if (!pb.loaded[k] && !(pb.nsym > 0 && pb.krep[k] != k))
+      return fail(c, TC_ERR_STATE, "orbitals of k-point " + std::to_string(k) + " not loaded");
     nleft += pb.left[k];
   }
+  if (pb.nsym > 0 && (nleft != 0 || pb.nspin == 2))
+    return fail(c, TC_ERR_UNSUPPORTED, "symmetry is built for TC mode with one spin channel");
   if (nleft != 0 && nleft != pb.nk)
     return fail(c, TC_ERR_STATE, "left orbitals are loaded for some k-points only");
   pb.bitc = nleft == pb.nk;
@@ -1964,6 +2527,7 @@ int prepare(tc_ctx* c) {
     c->eng->upload_tables(pb, TableVariant{});
     c->tables_dirty = false;
   }
+  if (pb.nsym > 0 && !pb.sym_ready) return sym_prepare(c);
   return TC_OK;
 }
 
@@ -2023,7 +2587,10 @@ void run_apply(tc_ctx* c, void* out_dev, double* out_host) {
   const int P = pb.nspin * pb.P();   // orbitals of all spin channels (spin-major)
   alloc_shared(c);
   c->eng->prof = &c->prof;
-  c->eng->apply(c->stream, sh, pb, c->stage_ms);
+  if (pb.nsym > 0)
+    c->eng->apply_sym(c->stream, sh, pb, c->stage_ms);
+  else
+    c->eng->apply(c->stream, sh, pb, c->stage_ms);
   c->total_ms = 0;
   for (double v : c->stage_ms) c->total_ms += v;
   for (int sp = 0; sp < pb.nspin; ++sp) {
@@ -2056,6 +2623,7 @@ int do_apply(tc_ctx* c, void* out_dev, double* out_host) {
 int do_apply_vectors(tc_ctx* c, int nvec, const double* in_dev, double* out_dev) {
   if (nvec <= 0) return fail(c, TC_ERR_ARG, "nvec must be positive");
   if (c->pb.nspin == 2) return fail(c, TC_ERR_UNSUPPORTED, "trial vectors are built for unpolarised runs");
+  if (c->pb.nsym > 0) return fail(c, TC_ERR_UNSUPPORTED, "trial vectors are built without symmetry");
   int st = prepare(c);
   if (st != TC_OK) return st;
   alloc_shared(c);
@@ -2095,6 +2663,7 @@ int do_backward(tc_ctx* c, void* grad_dev, double* grad_host, double* dA, double
   int st = prepare(c);
   if (st != TC_OK) return st;
   if (pb.nspin == 2) return fail(c, TC_ERR_UNSUPPORTED, "the gradient is built for unpolarised runs");
+  if (pb.nsym > 0) return fail(c, TC_ERR_UNSUPPORTED, "the gradient is built without symmetry");
   if (!pb.bitc && (gl_dev || gl_host)) return fail(c, TC_ERR_ARG, "no left orbitals loaded: grad_left must be NULL");
   struct Keep {
     tc_ctx* c;
@@ -2246,6 +2815,7 @@ int begin_load(tc_ctx* c, int ik, int nband, const double* occ, int spin = 0) {
   c->sh.coef.alloc(size_t(2) * pb.nspin * pb.P() * pb.npw_max);   // spin-major: spin 0 first
   double* o = spin == 0 ? pb.occ.data() : pb.occ_dn.data();
   for (int b = 0; b < nband; ++b) o[size_t(ik) * nband + b] = occ[b];
+  pb.sym_ready = false;
   return TC_OK;
 }
 
@@ -2321,6 +2891,7 @@ int do_scf(tc_ctx* c, const tc_scf_params& prm, double* ehist, int* niter) {
   int st = prepare(c);
   if (st != TC_OK) return st;
   if (c->pb.nspin == 2) return fail(c, TC_ERR_UNSUPPORTED, "the self-consistent loop is built for unpolarised runs");
+  if (c->pb.nsym > 0) return fail(c, TC_ERR_UNSUPPORTED, "the self-consistent loop is built without symmetry");
   Problem& pb = c->pb;
   Shared& sh = c->sh;
   hipStream_t s = c->stream;
@@ -2513,6 +3084,7 @@ int tc_set_cell(tc_ctx* c, const double lat[9]) {
     for (int j = 0; j < 3; ++j)
       for (int k = 0; k < 3; ++k) pb.B[3 * j + k] = 2.0 * kPi * inv[3 * k + j];
     pb.cell = true;
+    pb.nsym = 0;   // operations are stated for a given cell, k-mesh and grid
     c->tables_dirty = true;
     c->have_result = false;
     return TC_OK;
@@ -2533,6 +3105,7 @@ int tc_set_kmesh(tc_ctx* c, int n1, int n2, int n3) {
     pb.left.assign(pb.nk, 0);
     pb.loaded_dn.assign(pb.nk, 0);
     pb.nb = 0;
+    pb.nsym = 0;
     c->tables_dirty = true;
     c->have_result = false;
     return TC_OK;
@@ -2544,6 +3117,7 @@ int tc_set_grid(tc_ctx* c, int N1, int N2, int N3) {
     if (N1 != N2 || N2 != N3 || !grid_supported(N1))
       return fail(c, TC_ERR_UNSUPPORTED, "only cubic grids N^3 with N in {8,12,16,24,32,48} are built");
     c->pb.N = N1;
+    c->pb.nsym = 0;
     c->tables_dirty = true;
     c->have_result = false;
     return TC_OK;
@@ -2561,6 +3135,7 @@ int tc_set_basis(tc_ctx* c, int ik, int npw, const int32_t* miller) {
     pb.miller[ik].assign(miller, miller + 3 * npw);
     pb.npw[ik] = npw;
     pb.loaded[ik] = 0;
+    pb.sym_ready = false;
     c->have_result = false;
     return TC_OK;
   });
@@ -2644,6 +3219,10 @@ int tc_set_nspin(tc_ctx* c, int nspin) {
     c->have_result = false;
     return TC_OK;
   });
+}
+
+int tc_set_symmetry(tc_ctx* c, int nsym, const int32_t* rot, const double* tau) {
+  return guard(c, [&]() -> int { return set_symmetry(c, nsym, rot, tau); });
 }
 
 int tc_load_orbitals_spin(tc_ctx* c, int spin, int ik, int nband, const double* right, const double* left,

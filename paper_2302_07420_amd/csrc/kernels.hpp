@@ -25,6 +25,7 @@ struct MeshInfo {
   int nb;           // bands per k-point of the occupied (partner) set
   int P;            // orbitals of one spin channel (nk * nb)
   int nbt;          // vectors per k-point of the target set (nb when the targets are the orbitals)
+  const int* tk = nullptr;   // k-point of target block j / nbt (device; null: the block index itself)
 };
 
 __device__ __forceinline__ int kindex_delta(const MeshInfo& mi, int kto, int kfrom) {
@@ -141,12 +142,12 @@ __global__ void k_scatter(const double* coef, const int* boxidx, const int* npw,
 // r -> G of per-target fields: out[j][g] (complex128) = field_j(box(g)) * scale, zero beyond npw
 template <typename R>
 __global__ void k_gather(const cx<R>* f, const int* boxidx, const int* npw, int nb, int npw_max, int j0, int nt,
-                         double scale, double* out, long nr) {
+                         double scale, double* out, long nr, const int* kmap = nullptr) {
   const long t = long(blockIdx.x) * blockDim.x + threadIdx.x;
   if (t >= long(nt) * npw_max) return;
   const int jt = int(t / npw_max), g = int(t - long(jt) * npw_max);
   const int j = j0 + jt;
-  const int ik = j / nb;
+  const int ik = kmap ? kmap[j / nb] : j / nb;   // kmap: k-point of target block j / nb
   double re = 0, im = 0;
   if (g < npw[ik]) {
     const cx<R> v = f[long(jt) * nr + boxidx[long(ik) * npw_max + g]];
@@ -325,7 +326,7 @@ struct FusedArgs {
 // index of the pair's shift in the kernel tables: k_jt - k_q (sign 1, target passes) or k_q - k_jt (sign 0);
 // target jt sits at k-point jt / nbt, partner q at q / nb
 __device__ __forceinline__ int pair_dindex(const MeshInfo& mi, int jt, int q, int sign) {
-  const int kt = jt / mi.nbt, kq = q / mi.nb;
+  const int kt = mi.tk ? mi.tk[jt / mi.nbt] : jt / mi.nbt, kq = q / mi.nb;
   return sign ? kindex_delta(mi, kt, kq) : kindex_delta(mi, kq, kt);
 }
 

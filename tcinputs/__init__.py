@@ -199,6 +199,152 @@ def polarized(w, seed, mix=0.3, occ_dn=None):
                      name=w.name + "_pol")
 
 
+# --------------------------------------------------------------------------
+# Crystal symmetry of the synthetic cells.  An operation {R | tau} maps fractional positions
+# x -> R (x + tau) (R integer, acting on lattice coordinates); k-point k0 maps to R^T k0 - b with b
+# integer such that the image lies in the mesh cell.  The orbital of the image is generated as
+# c_k(m) = c_k0(m0) exp(2 pi i (m - b).tau), m = R^T m0 + b (the convention of the C ABI).
+# --------------------------------------------------------------------------
+
+def _signed_permutations():
+    out = []
+    for perm in ((0, 1, 2), (0, 2, 1), (1, 0, 2), (1, 2, 0), (2, 0, 1), (2, 1, 0)):
+        for signs in range(8):
+            S = np.zeros((3, 3))
+            for i in range(3):
+                S[i, perm[i]] = -1.0 if (signs >> i) & 1 else 1.0
+            out.append(S)
+    return out
+
+
+def point_group_ops(lattice, cartesian=None):
+    """Integer matrices R (x -> R x, fractional) of the cubic rotations S (Cartesian) that map the lattice
+    onto itself, identity first; ``cartesian`` restricts S to a given list."""
+    L = np.asarray(lattice, dtype=np.float64)
+    Ss = _signed_permutations() if cartesian is None else cartesian
+    ops = []
+    for S in Ss:
+        R = np.linalg.inv(L.T) @ S @ L.T
+        Ri = np.rint(R)
+        if np.max(np.abs(R - Ri)) < 1e-9:
+            ops.append(Ri.astype(np.int32))
+    ops.sort(key=lambda R: (not np.array_equal(R, np.eye(3, dtype=np.int32)), R.tobytes()))
+    return ops
+
+
+def symmorphic_ops(lattice):
+    """(R, tau = 0) for the lattice's cubic point group (48 operations for the fcc and sc cells)."""
+    return [(R, np.zeros(3)) for R in point_group_ops(lattice)]
+
+
+def diamond_ops(lattice):
+    """The 48 operations of the diamond structure on the fcc lattice (atoms at 0 and (1/4,1/4,1/4) in
+    fractional coordinates): the 24 of T_d with tau = 0 and the 24 products with the inversion through the
+    bond centre, x -> -R x + w, w = (1/4,1/4,1/4), written as R' (x + tau) with R' = -R, tau = R'^-1 w."""
+    td = [S for S in _signed_permutations() if round(np.prod([S[i, np.argmax(np.abs(S[i]))] for i in range(3)])) == 1]
+    ops = [(R, np.zeros(3)) for R in point_group_ops(lattice, td)]
+    w = np.array([0.25, 0.25, 0.25])
+    for R, _ in list(ops):
+        Rp = -R
+        ops.append((Rp.astype(np.int32), np.linalg.solve(Rp.astype(np.float64), w)))
+    return ops
+
+
+def _map_k(R, kf, kmesh):
+    g = R.T @ kf
+    t = np.rint(g * np.asarray(kmesh)).astype(int)
+    assert np.max(np.abs(g * np.asarray(kmesh) - t)) < 1e-9, "operation does not map the mesh"
+    idx = np.mod(t, kmesh)
+    b = (t - idx) // np.asarray(kmesh)
+    return int((idx[0] * kmesh[1] + idx[1]) * kmesh[2] + idx[2]), b
+
+
+def k_orbits(ops, kmesh):
+    """Representative (lowest index of the orbit), operation index (-1 for a representative) and b for
+    every mesh k-point; the first listed operation that carries the representative onto k is used."""
+    kf = kmesh_fractions(*kmesh)
+    nk = len(kf)
+    rep, opi, bb = [-1] * nk, [-1] * nk, [np.zeros(3, int)] * nk
+    for k in range(nk):
+        if rep[k] >= 0:
+            continue
+        rep[k] = k
+        for o, (R, _) in enumerate(ops):
+            kk, b = _map_k(R, kf[k], kmesh)
+            if rep[kk] < 0:
+                rep[kk], opi[kk], bb[kk] = k, o, b
+    return rep, opi, bb
+
+
+def image_map(R, tau, b, miller_from, miller_to):
+    """(g0, phase) with coefficient g of the image = phase[g] * coefficient g0[g] of the source."""
+    look = {tuple(m): i for i, m in enumerate(np.asarray(miller_from))}
+    Rit = np.rint(np.linalg.inv(R.astype(np.float64)).T).astype(int)
+    g0 = np.empty(len(miller_to), dtype=np.int64)
+    ph = np.empty(len(miller_to), dtype=np.complex128)
+    for g, m in enumerate(np.asarray(miller_to)):
+        mb = m - b
+        g0[g] = look[tuple(Rit @ mb)]
+        ph[g] = np.exp(2j * math.pi * float(mb @ tau))
+    return g0, ph
+
+
+def symmetric_orbitals(w, ops, seed, strength=0.5, tries=50):
+    """Orbitals invariant under ``ops``: at each representative k-point the nb lowest eigenvectors of a
+    random Hermitian matrix (|k+G|^2/2 plus smooth random couplings) averaged over the operations that fix
+    the k-point, with a gap above the nb-th eigenvalue and wherever the filling changes (closed sets); the
+    other k-points' orbitals are
+    the images under the first operation carrying their representative onto them."""
+    rep, opi, bb = k_orbits(ops, w.kmesh)
+    kf = w.kfrac
+    B = reciprocal(w.lattice)
+    nb = w.nband
+    right = [None] * w.nk
+    rng = np.random.Generator(np.random.PCG64(seed))
+    for r in sorted(set(rep)):
+        M = np.asarray(w.miller[r])
+        n = M.shape[0]
+        little = []
+        for R, tau in ops:
+            kk, b = _map_k(R, kf[r], w.kmesh)
+            if kk == r:
+                g0, ph = image_map(R, tau, b, M, M)
+                O = np.zeros((n, n), dtype=np.complex128)
+                O[np.arange(n), g0] = ph
+                little.append(O)
+        kg = (M + kf[r][None, :]) @ B
+        t = 0.5 * np.sum(kg * kg, 1)
+        env = np.exp(-0.25 * t)
+        for _ in range(tries):
+            X = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+            H = np.diag(t) + strength * (X + X.conj().T) * np.outer(env, env)
+            Hs = sum(O @ H @ O.conj().T for O in little) / len(little)
+            ev, V = np.linalg.eigh(Hs)
+            # gaps above the set and wherever the filling changes inside it (bands of one filling closed)
+            f = np.asarray(w.occ[r], dtype=np.float64)
+            cuts = [nb] + [i for i in range(1, nb) if f[i] != f[i - 1]]
+            if all(ev[i] - ev[i - 1] > 1e-6 * max(1.0, abs(ev[i])) for i in cuts):
+                break
+        else:
+            raise RuntimeError(f"no closed set of {nb} bands at k-point {r}")
+        right[r] = np.ascontiguousarray(V[:, :nb].T)
+    for k in range(w.nk):
+        if rep[k] == k:
+            continue
+        R, tau = ops[opi[k]]
+        g0, ph = image_map(R, tau, bb[k], w.miller[rep[k]], w.miller[k])
+        right[k] = np.ascontiguousarray(right[rep[k]][:, g0] * ph[None, :])
+    occ = [np.asarray(w.occ[rep[k]], dtype=np.float64).copy() for k in range(w.nk)]
+    return w.replace(right=right, left=None, occ=occ, name=w.name + "_sym")
+
+
+def sym_arrays(ops):
+    """(rot [nsym][3][3] int32, tau [nsym][3] float64) as the C ABI takes them."""
+    rot = np.ascontiguousarray(np.stack([R for R, _ in ops]).astype(np.int32))
+    tau = np.ascontiguousarray(np.stack([np.asarray(t, dtype=np.float64) for _, t in ops]))
+    return rot, tau
+
+
 def grid_fits(miller_list, grid) -> bool:
     """True when every pair density is alias-free: N_i/2 >= 2 max|m_i| + 1."""
     mx = np.max(np.stack([np.max(np.abs(m), axis=0) for m in miller_list]), axis=0)
@@ -277,6 +423,9 @@ WORKLOADS = {
     # the fcc bench shape in the biorthogonal mode: left orbitals chi = phi + 0.1 z (z random, same
     # envelope, unit norm), biorthogonalised by the consumer
     "fcc_si_k444_g24_bitc": lambda: fcc_si(left_mix=0.1).replace(name="fcc_si_x1_k4x4x4_g24_bitc"),
+    # the fcc bench shape with orbitals invariant under the diamond structure's 48 operations (8 of the
+    # 64 k-points are representatives)
+    "fcc_si_k444_g24_sym": lambda: symmetric_orbitals(fcc_si(), diamond_ops(fcc_lattice(10.26)), SEED_BASE + 44),
 }
 
 
