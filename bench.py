@@ -32,7 +32,7 @@ HBM_PEAK_GBS = 8000.0
 # averaged over the launches of the step.  Keyed by kernel and by the hash of the library sources the
 # counters were taken on: any later change to those sources makes the figure stale (reported as null).
 MEASURED_TRAFFIC = {
-    ("k_fused_A<float,24>", "6958dd058c0e15ee"): 9.0355e9,
+    ("k_fused_A<float,24>", "55e561c46a8ce8b7"): 9.0851e9,
 }
 
 
@@ -55,7 +55,7 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def make_op(w, precision, stream):
+def make_op(w, precision, stream, symmetry=None):
     import torch
     import paper_2302_07420_amd as tc
 
@@ -67,6 +67,8 @@ def make_op(w, precision, stream):
         op.set_basis(ik, m)
     op.set_jastrow(w.A, w.C)
     op.set_options(precision, w.alpha, True, tc.TERM_ALL)
+    if symmetry:
+        op.set_symmetry(symmetry)
     # coefficients resident in HBM (torch owns the memory)
     keep = []
     for ik, c in enumerate(w.right):
@@ -162,6 +164,7 @@ def main():
     ap.add_argument("--no-split", action="store_true", help="skip the FP32 + split-BF16 (MFMA z-DFT) path")
     ap.add_argument("--no-bitc", action="store_true", help="skip the biorthogonal-mode side measurement")
     ap.add_argument("--no-scf", action="store_true", help="skip the block-Davidson SCF side measurement")
+    ap.add_argument("--no-sym", action="store_true", help="skip the crystal-symmetry side measurement")
     ap.add_argument("--workload", default="fcc_si_k444_g24",
                     help="named workload: fcc_si_k444_g24 (default), heg14_g16, heg54_twist2_g32, fcc_si_x2_k222_g48")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
@@ -251,6 +254,30 @@ def main():
         op_c.close()
         del keep_c
 
+    sym = None
+    if not args.no_sym and args.workload == "fcc_si_k444_g24":
+        # the same cell with orbitals invariant under the diamond structure's 48 operations: the
+        # symmetry-reduced path (occupied-occupied rows and targets at the 8 representative k-points of
+        # 64) against the unreduced path on the same inputs
+        ws = T.workload("fcc_si_k444_g24_sym")
+        ops = T.diamond_ops(ws.lattice)
+        res_y = {}
+        for name, prec, sops, nst in (("sym_fp32", tc.TC_PREC_FP32, ops, args.steps),
+                                      ("full_fp32", tc.TC_PREC_FP32, None, args.steps),
+                                      ("full_fp64", tc.TC_PREC_FP64, None, 1)):
+            op_y, keep_y = make_op(ws, prec, stream, sops)
+            ms_y, _, e_y, _ = time_steps(op_y, out, nst, 1)
+            res_y[name] = (ms_y, e_y[-1][0])
+            op_y.close()
+            del keep_y
+        ms_y, e_y = res_y["sym_fp32"]
+        sym = {"workload": ws.name, "operations": len(ops), "representative_kpoints": 8,
+               "value": ws.npairs / (ms_y / 1e3), "ms_per_step": ms_y, "energy_Ha": e_y,
+               "unreduced_fp32_ms_per_step": res_y["full_fp32"][0],
+               "speedup_vs_unreduced_fp32": res_y["full_fp32"][0] / ms_y,
+               "energy_rel_err_vs_unreduced_fp64": abs(e_y - res_y["full_fp64"][1]) / abs(res_y["full_fp64"][1])}
+        log(f"symmetry fp32: {ms_y:.2f} ms/step vs unreduced {res_y['full_fp32'][0]:.2f} ms/step, E = {e_y:.12f}")
+
     # dominant kernel and its roofline (algorithmic bytes / event-timed duration)
     dom = max(stats.items(), key=lambda kv: kv[1]["ms"])
     name, st = dom
@@ -306,6 +333,7 @@ def main():
         if split else None,
         "bitc_fp32_gpu": bitc,
         "scf_davidson_gpu": scf,
+        "symmetry_fp32_gpu": sym,
         "stages_ms": dict(zip(tc.STAGES, stages)),
         "kernels_ms_per_step": per_kernel,
         "kernel_ms_per_step_total": total_kernel_ms,
