@@ -157,6 +157,30 @@ int tc_load_orbitals_dev(tc_ctx* ctx, int ik, int nband, const void* right_dev, 
  * TC_ERR_ARG unless nspin is 1 or 2; TC_ERR_STATE before the k-mesh. */
 int tc_set_nspin(tc_ctx* ctx, int nspin);
 
+/* Band (zero-weight) k-points (Sec. 2.5 and the band forms of Sec. 2.6): k-points anywhere, not on the
+ * SCF mesh, whose orbitals are targets of the operator of the loaded (mesh) orbitals and partners of none.
+ * kfrac: nkb fractional k-points (units of the reciprocal rows, no reduction); 0 <= nkb <= 4096.  Call
+ * after the k-mesh; it discards the band bases and orbitals; setting the k-mesh again removes them.
+ * TC_ERR_ARG for a bad count or null k-points, TC_ERR_STATE before the k-mesh. */
+int tc_set_band_kpoints(tc_ctx* ctx, int nkb, const double* kfrac);
+
+/* Plane-wave set of band k-point ib (as tc_set_basis: npw Miller triples inside the grid). */
+int tc_set_band_basis(tc_ctx* ctx, int ib, int npw, const int32_t* miller);
+
+/* Orbitals of band k-point ib: nband x npw(ib) complex128 coefficients (the same nband at every band
+ * k-point) and their fillings in [0, 1], which the divergence corrections of the band forms use.  All band
+ * bases must be set first (TC_ERR_STATE). */
+int tc_load_band_orbitals(tc_ctx* ctx, int ib, int nband, const double* coef, const double* occ);
+
+/* Apply the two- and three-body operator of the loaded mesh orbitals (Eq. SCF with the selected terms) to
+ * every band orbital: out (host, may be NULL) receives [nkb][nband][npw_max_band] complex128 (H c)(G) on
+ * each band k-point's plane waves, zero-padded; eps (host, may be NULL) [nkb][nband] complex128 orbital
+ * energies <phi| T + h |phi>.  The shift of each pair is k_b - k_q exactly (no reduction modulo G).  The
+ * band forms of the divergence corrections are not built: with div_correction set and the correction
+ * bit selected this returns TC_ERR_UNSUPPORTED.  TC mode, one spin channel, no symmetry
+ * (TC_ERR_UNSUPPORTED otherwise). */
+int tc_apply_band(tc_ctx* ctx, double* out, double* eps);
+
 /* Crystal symmetry (Sec. 2.6.1: the orbital of k = R^T k0 - b is the image of that of k0; Sec. 2.6.4: the
  * fields h5 and h3 of the occupied-occupied pass of Algs. 3a2 and 3a4 are computed for irreducible
  * k-points only and rotated).  nsym operations x -> R (x + tau) on fractional (lattice) coordinates x:

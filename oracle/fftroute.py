@@ -117,6 +117,13 @@ class Problem:
         n1, n2, n3 = self.kmesh
         self.kfrac = np.array([(i1 / n1, i2 / n2, i3 / n3) for i1 in range(n1)
                                for i2 in range(n2) for i3 in range(n3)])
+        # band (zero-weight) k-points off the mesh (Sec. 2.5, band-structure calculation): their
+        # orbitals are targets of every term and partners of none; their fillings enter only the
+        # divergence corrections.  k indices nk .. nk + nkb - 1.
+        bk = getattr(w, "band_k", None)
+        self.nkb = 0 if bk is None else len(bk)
+        self.kall = self.kfrac if not self.nkb else np.concatenate(
+            [self.kfrac, np.asarray(bk, dtype=np.float64).reshape(-1, 3)])
         self.grid = tuple(int(x) for x in w.grid)
         self.nr = int(np.prod(self.grid))
         self.alpha = float(w.alpha if alpha is None else alpha)
@@ -159,6 +166,9 @@ class Problem:
         else:
             self.spin_sets = [(cr, cl, self.occ)] * 2
         self.miller = [np.asarray(m, dtype=np.int64) for m in w.miller]
+        if self.nkb:
+            assert cl is None and not self.polarized, "band k-points are built for TC mode with one spin channel"
+            self.miller += [np.asarray(m, dtype=np.int64) for m in w.band_miller]
         self._build_orbitals()
         self._gb()
 
@@ -180,7 +190,7 @@ class Problem:
         m = self.miller[ik]
         nb = c.shape[0]
         if grad:
-            kg = torch.as_tensor((self.kfrac[ik][None, :] + m) @ self.B, dtype=RD)  # (npw,3)
+            kg = torch.as_tensor((self.kall[ik][None, :] + m) @ self.B, dtype=RD)  # (npw,3)
             out = []
             for a in range(3):
                 box = torch.zeros((nb, N1, N2, N3), dtype=CD)
@@ -200,15 +210,27 @@ class Problem:
             D.append(self._to_real(cr[ik], ik, grad=True))
             kidx += [ik] * p.shape[0]
             f.append(occ[ik])
+        w = torch.cat(f) / self.nk
+        for b in range(self.nkb):   # band orbitals: fillings for the corrections, zero partner weight
+            ik = self.nk + b
+            c = torch.as_tensor(self.w.band_right[b], dtype=CD)
+            p = self._to_real(c, ik)
+            phi.append(p)
+            chi.append(p)
+            D.append(self._to_real(c, ik, grad=True))
+            kidx += [ik] * p.shape[0]
+            f.append(torch.as_tensor(self.w.band_occ[b], dtype=RD))
         f = torch.cat(f)
-        return dict(phi=torch.cat(phi), chi=torch.cat(chi), D=torch.cat(D), f=f, w=f / self.nk,
+        w = torch.cat([w, torch.zeros(f.shape[0] - w.shape[0], dtype=RD)])
+        return dict(phi=torch.cat(phi), chi=torch.cat(chi), D=torch.cat(D), f=f, w=w,
                     k=np.array(kidx, dtype=np.int64))
 
     def _build_orbitals(self):
         # one orbital set per spin channel; unpolarized input: both channels hold the same orbitals
         up = self._channel(*self.spin_sets[0])
         self.orb = [up, self._channel(*self.spin_sets[1]) if self.polarized else up]
-        self.P = up["phi"].shape[0]
+        self.P = up["phi"].shape[0]                      # targets: mesh and band orbitals
+        self.Pm = int(np.sum(up["k"] < self.nk))           # partners: the mesh orbitals
         assert self.orb[1]["phi"].shape[0] == self.P, "the same number of bands per spin channel is assumed"
         self.n = [torch.sum(o["w"][:, None, None, None] * torch.conj(o["chi"]) * o["phi"], 0)
                   for o in self.orb]
@@ -277,6 +299,32 @@ class Problem:
         self.gb_vector = vec / self.nk
         self.delta_gb = self.omega / (4.0 * math.sqrt(math.pi ** 3 * a)) - (-a + tot) / self.nk
 
+    def gb_band(self, ik):
+        """GB quantities at a band k-point (off the mesh, so no k - q + G vanishes): the bracket of
+        Eq. correction with the mesh sum S = sum_{q,G} A_aux(k - q + G), divided by 4 pi as delta_gb is,
+        and the vector sum of Eq. correction_nabla taken at the same arguments (reading R13),
+        V = sum_{q,G} (k - q + G) A_aux(k - q + G) (Cartesian).  Returns (delta_gb_band, V / N_k)."""
+        key = ("gb_band", ik)
+        if key in self._kcache:
+            return self._kcache[key]
+        a = self.alpha
+        qmax = math.sqrt(41.45 / a)
+        lens = np.linalg.norm(self.lattice, axis=1)
+        mmax = [int(math.ceil(qmax * L / (2 * math.pi))) + 3 for L in lens]
+        rr = [np.arange(-m, m + 1) for m in mmax]
+        M = np.stack(np.meshgrid(*rr, indexing="ij"), -1).reshape(-1, 3).astype(np.float64)
+        tot, vec = 0.0, np.zeros(3)
+        for q in self.kfrac:
+            Q = (M + (self.kall[ik] - q)[None, :]) @ self.B
+            q2 = np.sum(Q * Q, 1)
+            ok = a * q2 < 41.45
+            t = np.exp(-a * q2[ok]) / q2[ok]
+            tot += math.fsum(t)
+            vec += (Q[ok] * t[:, None]).sum(0)
+        out = (self.omega / (4.0 * math.sqrt(math.pi ** 3 * a)) - tot / self.nk, vec / self.nk)
+        self._kcache[key] = out
+        return out
+
     # ---------------------------------------------------------------- helpers
     def sel(self, s, ik=None):
         o = self.orb[s]
@@ -312,7 +360,7 @@ class Problem:
         raise ValueError(kind)
 
     def dk(self, kt, kq):
-        return self.kfrac[kt] - self.kfrac[kq]
+        return self.kall[kt] - self.kall[kq]
 
     # ---------------------------------------------------------------- two-body
     def t_2ah(self, s):
@@ -333,8 +381,8 @@ class Problem:
     def _exchange_loop(self, s, body):
         o = self.orb[s]
         acc = {}
-        for q in range(self.P):
-            for kt in range(self.nk):
+        for q in range(self.Pm):
+            for kt in range(self.nk + self.nkb):
                 J = self.sel_t(s, kt)
                 if len(J) == 0:
                     continue
@@ -368,7 +416,9 @@ class Problem:
                 continue
             Q = self.sel(s, o["k"][j])
             r0 = self.rho0(torch.conj(o["chi"][Q]), o["phi"][j][None])   # (nb,)
-            out.append(-FOURPI * self.delta_gb * torch.sum((o["f"][Q] * r0)[:, None, None, None] * o["phi"][Q], 0))
+            # band k-point: Eq. divcorr_2ax_band (no excluded term and no alpha)
+            dgb = self.delta_gb if o["k"][j] < self.nk else self.gb_band(o["k"][j])[0]
+            out.append(-FOURPI * dgb * torch.sum((o["f"][Q] * r0)[:, None, None, None] * o["phi"][Q], 0))
         return torch.stack(out)
 
     def t_2bx1(self, s):
@@ -406,8 +456,8 @@ class Problem:
         o2 = self.orb[s2]
         ch = _pair(s, s2)
         h5 = 0
-        for q1 in range(self.P):
-            d21 = self.kfrac[o2["k"][q1]] - self.kfrac[o2["k"][q2]]
+        for q1 in range(self.Pm):
+            d21 = self.kall[o2["k"][q1]] - self.kall[o2["k"][q2]]
             h2 = self.conv(d21, "X", ch, self.FT(torch.conj(o2["chi"][q2]) * o2["phi"][q1]), "U")
             h4 = self.conv(-d21, "X", ch, self.FT(torch.conj(o2["chi"][q1]) * o2["phi"][q2]), "U")
             h5 = h5 + torch.sum(h2 * h4, 0) * o2["w"][q1]
@@ -436,7 +486,7 @@ class Problem:
         """Alg. 3a2: g_j = h6 phi_j / 2 with h6 = sum_s2 sum_q2 w_q2 h5^{s,s2}(q2)."""
         h6 = 0
         for s2 in range(2):
-            for q2 in range(self.P):
+            for q2 in range(self.Pm):
                 h6 = h6 + self.h5_3a2(s, q2, s2) * self.orb[s2]["w"][q2]
         return 0.5 * h6[None] * self.orb[s]["phi"]
 
@@ -444,7 +494,7 @@ class Problem:
         """h4 of Alg. 3a3 for target j (equals h3 of Alg. 3b4, reading R5)."""
         o = self.orb[s]
         h4 = 0
-        for q1 in range(self.P):
+        for q1 in range(self.Pm):
             d = self.dk(o["k"][j], o["k"][q1])
             h3 = self.conv(d, "X", 0, self.FT(torch.conj(o["chi"][q1]) * o["phi"][j]), "U")
             h4 = h4 + h3 * o["phi"][q1][None] * o["w"][q1]
@@ -461,8 +511,8 @@ class Problem:
         """h3^{s2}(r; q2) of Alg. 3a4 (q2 of spin s, same-spin partners q1)."""
         o = self.orb[s]
         h3 = 0
-        for q1 in range(self.P):
-            d = self.kfrac[o["k"][q2]] - self.kfrac[o["k"][q1]]
+        for q1 in range(self.Pm):
+            d = self.kall[o["k"][q2]] - self.kall[o["k"][q1]]
             h2 = self.conv(d, "X", 0, self.FT(torch.conj(o["chi"][q1]) * o["phi"][q2]), "U")
             h3 = h3 + h2 * o["phi"][q1][None] * o["w"][q1]
         return h3
@@ -471,9 +521,9 @@ class Problem:
         """Alg. 3a4: g_j = -1/2 sum_q2 w_q2 h3(q2) . [iQu~ (*) chi_q2^* phi_j]."""
         o = self.orb[s]
         g = torch.zeros_like(o["phi"])
-        for q2 in range(self.P):
+        for q2 in range(self.Pm):
             h3 = self.h3_3a4(s, q2)
-            for kt in range(self.nk):
+            for kt in range(self.nk + self.nkb):
                 J = self.sel_t(s, kt)
                 if len(J) == 0:
                     continue
@@ -494,8 +544,8 @@ class Problem:
         """h3^{s2}(r; q2) of Algs. 3b2 / 3b5."""
         o = self.orb[s2]
         h3 = 0
-        for q1 in range(self.P):
-            d = self.kfrac[o["k"][q1]] - self.kfrac[o["k"][q2]]
+        for q1 in range(self.Pm):
+            d = self.kall[o["k"][q1]] - self.kall[o["k"][q2]]
             h2 = self.conv(d, "X", 0, self.FT(torch.conj(o["chi"][q2]) * o["phi"][q1]), "U")
             h3 = h3 + h2 * torch.conj(o["chi"][q1])[None] * o["w"][q1]
         return h3
@@ -506,7 +556,7 @@ class Problem:
         for s2 in range(2):
             o2 = self.orb[s2]
             h5 = 0
-            for q2 in range(self.P):
+            for q2 in range(self.Pm):
                 h5 = h5 + self.h3_3b2(s2, q2) * o2["phi"][q2][None] * o2["w"][q2]
             h6 = h6 + self.conv(np.zeros(3), "H", _pair(s, s2), self.FT(h5), "Ud")
         return 0.5 * h6[None] * self.orb[s]["phi"]
@@ -532,7 +582,7 @@ class Problem:
                 continue
             h3 = self.h4_3a3(s, j)
             acc = 0
-            for q1 in range(self.P):
+            for q1 in range(self.Pm):
                 d = self.dk(o["k"][j], o["k"][q1])
                 h4 = h3 * torch.conj(o["chi"][q1])[None]
                 h5 = self.conv(d, "X", 0, self.FT(h4), "Ud")
@@ -544,9 +594,9 @@ class Problem:
         """Alg. 3b5 with the sign of its caption, the term list and Eq. 3b5_div (reading R9)."""
         o = self.orb[s]
         g = torch.zeros_like(o["phi"])
-        for q2 in range(self.P):
+        for q2 in range(self.Pm):
             h3 = self.h3_3b2(s, q2)
-            for kt in range(self.nk):
+            for kt in range(self.nk + self.nkb):
                 J = self.sel_t(s, kt)
                 if len(J) == 0:
                     continue
@@ -642,12 +692,12 @@ class Problem:
         """Pseudo-energy per cell (reading R8), summed over both spin channels."""
         parts = {}
         for s in range(2):
-            f = self.orb[s]["f"]
+            f = self.orb[s]["f"][:self.Pm]   # mesh orbitals only (band orbitals carry no weight)
             if with_kinetic:
                 parts["T"] = parts.get("T", 0) + torch.sum(f * self.kinetic(s)).real / self.nk
             for t in terms:
                 fac = 0.5 if t in TERMS2 else MULT[t] / 3.0
-                e = torch.sum(f * self.braket(s, self.term(t, s))).real * fac / self.nk
+                e = torch.sum(f * self.braket(s, self.term(t, s))[:self.Pm]).real * fac / self.nk
                 parts[t] = parts.get(t, 0) + e
         tot = sum(parts.values())
         return (tot, parts) if per_term else tot
@@ -656,7 +706,7 @@ class Problem:
         """(Hc)(G) = sqrt(Omega) FT[g](G) on each orbital's plane-wave set."""
         o = self.orb[s]
         out = []
-        for ik in range(self.nk):
+        for ik in range(self.nk + self.nkb):
             J = self.sel(s, ik)
             m = self.miller[ik]
             N1, N2, N3 = self.grid

@@ -70,6 +70,10 @@ def lib():
         "tc_load_orbitals": (I, [P, I, I, dp, dp, dp]),
         "tc_set_nspin": (I, [P, I]),
         "tc_set_symmetry": (I, [P, I, ctypes.POINTER(ctypes.c_int32), dp]),
+        "tc_set_band_kpoints": (I, [P, I, dp]),
+        "tc_set_band_basis": (I, [P, I, I, ctypes.POINTER(ctypes.c_int32)]),
+        "tc_load_band_orbitals": (I, [P, I, I, dp, dp]),
+        "tc_apply_band": (I, [P, dp, dp]),
         "tc_load_orbitals_spin": (I, [P, I, I, I, dp, dp, dp]),
         "tc_orbital_energies": (I, [P, dp]),
         "tc_apply": (I, [P, I, dp, dp]),
@@ -173,6 +177,33 @@ class TCOperator:
         tau = np.ascontiguousarray(np.stack([np.asarray(t, dtype=np.float64) for _, t in ops]))
         self._check(self._L.tc_set_symmetry(self._h, len(ops), rot.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
                                             _dp(tau)), "tc_set_symmetry")
+
+    def set_band(self, kpoints, millers, coeffs, occs):
+        """Band (zero-weight) k-points: fractional k (nkb, 3), per band k-point its Miller set, orbitals
+        (nband, npw) and fillings."""
+        k = np.ascontiguousarray(np.asarray(kpoints, dtype=np.float64).reshape(-1, 3))
+        self._check(self._L.tc_set_band_kpoints(self._h, k.shape[0], _dp(k)), "tc_set_band_kpoints")
+        self.band_npw = []
+        for ib, m in enumerate(millers):
+            mm = np.ascontiguousarray(np.asarray(m, dtype=np.int32).reshape(-1, 3))
+            self._check(self._L.tc_set_band_basis(self._h, ib, mm.shape[0],
+                                                  mm.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))), "tc_set_band_basis")
+            self.band_npw.append(mm.shape[0])
+        for ib, (c, o) in enumerate(zip(coeffs, occs)):
+            cc = np.ascontiguousarray(np.asarray(c, dtype=np.complex128))
+            oo = np.ascontiguousarray(np.asarray(o, dtype=np.float64))
+            self._check(self._L.tc_load_band_orbitals(self._h, ib, cc.shape[0], _dp(cc.view(np.float64)), _dp(oo)),
+                        "tc_load_band_orbitals")
+            self.band_nb = cc.shape[0]
+
+    def apply_band(self):
+        """(H c per band k-point as (nband, npw) arrays, orbital energies [nkb, nband])."""
+        nkb, nb, npm = len(self.band_npw), self.band_nb, max(self.band_npw)
+        out = np.zeros((nkb, nb, npm), dtype=np.complex128)
+        eps = np.zeros((nkb, nb), dtype=np.complex128)
+        self._check(self._L.tc_apply_band(self._h, _dp(out.view(np.float64)), _dp(eps.view(np.float64))),
+                    "tc_apply_band")
+        return [out[b, :, : self.band_npw[b]].copy() for b in range(nkb)], eps
 
     def load_orbitals(self, ik, coeff, occ, left=None, spin=0):
         """Right orbitals ``coeff`` (nband, npw) of k-point ik; ``left`` (same shape) switches that k-point to
@@ -354,6 +385,8 @@ def from_workload(w, precision=TC_PREC_FP64, terms=TERM_ALL, div_correction=True
         if dn is not None:
             occd = w.occ_dn if w.occ_dn is not None else w.occ
             op.load_orbitals(ik, dn[ik], occd[ik], spin=1)
+    if getattr(w, "band_k", None) is not None:
+        op.set_band(w.band_k, w.band_miller, w.band_right, w.band_occ)
     return op
 
 

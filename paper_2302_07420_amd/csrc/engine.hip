@@ -175,6 +175,14 @@ struct Problem {
   std::vector<int> krep, kop, kb;         // per k: representative, operation (-1: itself), b [3]
   std::vector<int> irr;                   // representative k-points, increasing
   bool sym_ready = false;                 // the other k-points' orbitals generated since the last load
+  // band (zero-weight) k-points (tc_set_band_kpoints): fractional k, plane waves, orbitals' fillings
+  int nkb = 0;
+  std::vector<double> bk;                 // [nkb][3]
+  std::vector<std::vector<int>> bmiller;  // per band k, 3*npw
+  std::vector<int> bnpw;
+  int bnb = 0;                            // orbitals per band k-point
+  std::vector<double> bocc;               // [nkb][bnb]
+  std::vector<char> bloaded;
 
   int P() const { return nk * nb; }
   long NR() const { return long(N) * N * N; }
@@ -273,6 +281,10 @@ struct Shared {                       // precision-independent device data
   DBuf<int> irrk, symg0;                // [nirr], [nk][npw_max]
   DBuf<double> symph;                   // [nk][npw_max] complex phases
   DBuf<double> outI, epartI;            // [nirr nb][npw_max] complex, [nirr nb][kAccSlots]
+  // band k-points: coefficients [nkb][bnb][bnpm] (complex128), plane-wave data, k codes, output, energies
+  DBuf<double> bcoef, bkg, bout, beps;
+  DBuf<int> bbox, bnpwd, btk;
+  int bnpm = 0;
 };
 
 // ------------------------------------------------------------------ FP64 helper kernels
@@ -747,6 +759,14 @@ struct TargetSet {
   const double* coef = nullptr;
   int nvec = 0;
   double* out = nullptr;
+  // band targets (tc_apply_band): nblk k-points coded tk[] = nk + b, with their own plane-wave data
+  int nblk = 0;                         // 0: one block per mesh k-point
+  const int* tk = nullptr;
+  const int* boxidx = nullptr;
+  const int* npw = nullptr;
+  const double* kg = nullptr;
+  int npm = 0;
+  bool band = false;
 };
 
 struct Engine {
@@ -897,9 +917,26 @@ struct EngineT : Engine {
     std::vector<R> V(size_t(nD) * NR), U1(size_t(nD) * NR), U2(size_t(nD) * NR);
     std::vector<double> df(size_t(nD) * 3);
     const int e2 = 2 * pb.n2 - 1, e3 = 2 * pb.n3 - 1;
-    parallel_for(nD, [&](int di) {
-      const int d1 = di / (e2 * e3) - (pb.n1 - 1), d2 = (di / e3) % e2 - (pb.n2 - 1), d3 = di % e3 - (pb.n3 - 1);
-      const double f[3] = {double(d1) / pb.n1, double(d2) / pb.n2, double(d3) / pb.n3};
+    // after the mesh differences: band k-points, Delta = k_b - k_q (all b, q) then k_q - k_b
+    const int nBand = 2 * pb.nkb * pb.nk;
+    V.resize(size_t(nD + nBand) * NR);
+    U1.resize(V.size());
+    U2.resize(V.size());
+    df.resize(size_t(nD + nBand) * 3);
+    parallel_for(nD + nBand, [&](int di) {
+      double f[3];
+      if (di < nD) {
+        const int d1 = di / (e2 * e3) - (pb.n1 - 1), d2 = (di / e3) % e2 - (pb.n2 - 1), d3 = di % e3 - (pb.n3 - 1);
+        f[0] = double(d1) / pb.n1;
+        f[1] = double(d2) / pb.n2;
+        f[2] = double(d3) / pb.n3;
+      } else {
+        const int x = di - nD, sgn = x < pb.nkb * pb.nk ? 1 : -1, y = x % (pb.nkb * pb.nk);
+        const int b = y / pb.nk, q = y % pb.nk;
+        double fq[3];
+        pb.kfrac(q, fq);
+        for (int c = 0; c < 3; ++c) f[c] = sgn * (pb.bk[3 * b + c] - fq[c]);
+      }
       for (int c = 0; c < 3; ++c) df[3 * size_t(di) + c] = f[c];
       fill_delta(pb, tv, f, scale, &V[size_t(di) * NR], &U1[size_t(di) * NR], &U2[size_t(di) * NR]);
     });
@@ -1106,9 +1143,15 @@ struct EngineT : Engine {
     ensure(pb, size_t(8) << 30);
     // targets: the orbitals, or nbt trial vectors per k-point
     const int nbt = ts ? ts->nvec : nb;
-    const int NTG = pb.nk * nbt;
+    const int NTG = (ts && ts->nblk ? ts->nblk : pb.nk) * nbt;
     const MeshInfo mi{pb.n1, pb.n2, pb.n3, nb, P, nb};     // occupied-occupied pass
-    const MeshInfo miT{pb.n1, pb.n2, pb.n3, nb, P, nbt};   // target passes
+    const MeshInfo miT{pb.n1, pb.n2, pb.n3, nb, P, nbt, ts ? ts->tk : nullptr, pb.nkb};   // target passes
+    // plane-wave data of the targets (band targets carry their own)
+    const bool tb_own = ts && ts->boxidx;
+    const int* tbox = tb_own ? ts->boxidx : sh.boxidx.p;
+    const int* tnpw = tb_own ? ts->npw : sh.npw.p;
+    const double* tkg = tb_own ? ts->kg : sh.kg.p;
+    const int tnpm = tb_own ? ts->npm : pb.npw_max;
     Recip rc;
     for (int i = 0; i < 9; ++i) rc.b[i] = pb.B[i];
     Basis<R> bm, mm;   // B_dc = (b_d)_c and the metric M = B B^T, working precision
@@ -1155,13 +1198,13 @@ struct EngineT : Engine {
       DT.alloc(size_t(3) * NTG * NR);
       TC_HIP(hipMemsetAsync(psiT.p, 0, size_t(NTG) * NR * sizeof(cx<R>), s));
       TC_HIP(hipMemsetAsync(DT.p, 0, size_t(3) * NTG * NR * sizeof(cx<R>), s));
-      const unsigned gst = nblk(long(NTG) * pb.npw_max);
+      const unsigned gst = nblk(long(NTG) * tnpm);
       K(TC_K_SCATTER, 0.0, [&] {
-        hipLaunchKernelGGL((k_scatter<R>), dim3(gst), dim3(256), 0, s, ts->coef, sh.boxidx.p, sh.npw.p, sh.kg.p, nbt,
-                           pb.npw_max, NTG, -1, psiT.p, NR);
+        hipLaunchKernelGGL((k_scatter<R>), dim3(gst), dim3(256), 0, s, ts->coef, tbox, tnpw, tkg, nbt, tnpm, NTG, -1,
+                           psiT.p, NR);
         for (int c = 0; c < 3; ++c)
-          hipLaunchKernelGGL((k_scatter<R>), dim3(gst), dim3(256), 0, s, ts->coef, sh.boxidx.p, sh.npw.p, sh.kg.p,
-                             nbt, pb.npw_max, NTG, c, DT.p + size_t(c) * NTG * NR, NR);
+          hipLaunchKernelGGL((k_scatter<R>), dim3(gst), dim3(256), 0, s, ts->coef, tbox, tnpw, tkg, nbt, tnpm, NTG, c,
+                             DT.p + size_t(c) * NTG * NR, NR);
       });
       fft3d_t<R, N>(psiT.p, NTG, +1, s, pf);
       fft3d_t<R, N>(DT.p, 3L * NTG, +1, s, pf);
@@ -1355,8 +1398,8 @@ struct EngineT : Engine {
       });
       fft3d_t<R, N>(g.p, nt, -1, s, pf);
       K(TC_K_OTHER, 0.0, [&] {
-        hipLaunchKernelGGL((k_gather<R>), dim3(nblk(long(nt) * pb.npw_max)), dim3(256), 0, s, g.p, sh.boxidx.p,
-                           sh.npw.p, nbt, pb.npw_max, t0, nt, 1.0 / double(NR), ts ? ts->out : sh.out.p, NR);
+        hipLaunchKernelGGL((k_gather<R>), dim3(nblk(long(nt) * tnpm)), dim3(256), 0, s, g.p, tbox, tnpw, nbt, tnpm,
+                           t0, nt, 1.0 / double(NR), ts ? ts->out : sh.out.p, NR);
       });
     }
     TC_HIP(hipEventRecord(ev.e[4], s));
@@ -1368,7 +1411,8 @@ struct EngineT : Engine {
                            sh.npw.p, nb, pb.npw_max, sh.tkin.p);
         TC_HIP(hipMemsetAsync(sh.ecorr.p, 0, size_t(2) * P * sizeof(double), s));
       }
-      if (pb.div && (pb.mask & TC_T_CORR) && (m.m2ax || m.m3a2 || m.m3b6)) corrections(s, sh, pb, m, ts);
+      if (pb.div && (pb.mask & TC_T_CORR) && (m.m2ax || m.m3a2 || m.m3b6) && !(ts && ts->band))
+        corrections(s, sh, pb, m, ts);
     });
     TC_HIP(hipEventRecord(ev.e[5], s));
     TC_HIP(hipEventSynchronize(ev.e[5]));
@@ -2194,6 +2238,133 @@ int guard(tc_ctx* c, F&& f) {
 bool grid_supported(int N) { return N == 8 || N == 12 || N == 16 || N == 24 || N == 32 || N == 48; }
 
 void upload_basis_data(tc_ctx* c);
+int prepare(tc_ctx* c);
+void alloc_shared(tc_ctx* c);
+// ------------------------------------------------------------------ band (zero-weight) k-points
+int set_band_kpoints(tc_ctx* c, int nkb, const double* kfrac) {
+  Problem& pb = c->pb;
+  if (pb.nk == 0) return fail(c, TC_ERR_STATE, "set the k-mesh before band k-points");
+  if (nkb < 0 || nkb > 4096 || (nkb > 0 && !kfrac)) return fail(c, TC_ERR_ARG, "0 <= nkb <= 4096 and k-points needed");
+  pb.nkb = nkb;
+  pb.bk.assign(kfrac, kfrac + 3 * size_t(nkb));
+  pb.bmiller.assign(nkb, {});
+  pb.bnpw.assign(nkb, 0);
+  pb.bnb = 0;
+  pb.bocc.clear();
+  pb.bloaded.assign(nkb, 0);
+  c->tables_dirty = true;   // band shift tables
+  return TC_OK;
+}
+
+int set_band_basis(tc_ctx* c, int ib, int npw, const int32_t* miller) {
+  Problem& pb = c->pb;
+  if (pb.N == 0) return fail(c, TC_ERR_STATE, "set the grid first");
+  if (ib < 0 || ib >= pb.nkb || npw <= 0 || !miller) return fail(c, TC_ERR_ARG, "bad band basis arguments");
+  for (int g = 0; g < 3 * npw; ++g)
+    if (miller[g] >= pb.N / 2 || miller[g] < -(pb.N / 2) + 1)
+      return fail(c, TC_ERR_GRID, "plane wave outside the FFT grid");
+  pb.bmiller[ib].assign(miller, miller + 3 * size_t(npw));
+  pb.bnpw[ib] = npw;
+  std::fill(pb.bloaded.begin(), pb.bloaded.end(), 0);   // the coefficient layout follows max npw
+  return TC_OK;
+}
+
+int load_band_orbitals(tc_ctx* c, int ib, int nband, const double* coef, const double* occ) {
+  Problem& pb = c->pb;
+  Shared& sh = c->sh;
+  if (ib < 0 || ib >= pb.nkb) return fail(c, TC_ERR_ARG, "band k-point index out of range");
+  for (int b = 0; b < pb.nkb; ++b)
+    if (pb.bnpw[b] <= 0) return fail(c, TC_ERR_STATE, "tc_set_band_basis missing for band k-point " + std::to_string(b));
+  if (nband <= 0 || !coef || !occ) return fail(c, TC_ERR_ARG, "nband must be positive, coef and occ non-null");
+  if (nband > pb.bnpw[ib]) return fail(c, TC_ERR_ARG, "more bands than plane waves");
+  for (int b = 0; b < nband; ++b)
+    if (!(occ[b] >= 0.0 && occ[b] <= 1.0)) return fail(c, TC_ERR_ARG, "fillings must lie in [0, 1]");
+  if (pb.bnb != nband) {
+    pb.bnb = nband;
+    std::fill(pb.bloaded.begin(), pb.bloaded.end(), 0);
+  }
+  pb.bocc.resize(size_t(pb.nkb) * nband);
+  for (int b = 0; b < nband; ++b) pb.bocc[size_t(ib) * nband + b] = occ[b];
+  int mx = 0;
+  for (int b = 0; b < pb.nkb; ++b) mx = std::max(mx, pb.bnpw[b]);
+  if (mx != sh.bnpm || sh.bcoef.n < size_t(2) * pb.nkb * nband * mx) {
+    sh.bcoef.alloc(size_t(2) * pb.nkb * nband * mx);
+    std::fill(pb.bloaded.begin(), pb.bloaded.end(), 0);
+  }
+  sh.bnpm = mx;
+  std::vector<double> stage(size_t(2) * nband * mx, 0.0);
+  for (int b = 0; b < nband; ++b)
+    std::memcpy(&stage[size_t(2) * b * mx], coef + size_t(2) * b * pb.bnpw[ib], size_t(2) * pb.bnpw[ib] * sizeof(double));
+  TC_HIP(hipMemcpy(sh.bcoef.p + size_t(2) * ib * nband * mx, stage.data(), stage.size() * sizeof(double),
+                   hipMemcpyHostToDevice));
+  pb.bloaded[ib] = 1;
+  return TC_OK;
+}
+
+// The operator of the loaded (mesh) orbitals applied to the orbitals of the band k-points, and their
+// orbital energies.
+int do_apply_band(tc_ctx* c, double* out_host, double* eps_host) {
+  Problem& pb = c->pb;
+  Shared& sh = c->sh;
+  if (pb.nkb == 0) return fail(c, TC_ERR_STATE, "no band k-points set");
+  int st = prepare(c);
+  if (st != TC_OK) return st;
+  if (pb.bitc || pb.nspin == 2 || pb.nsym > 0)
+    return fail(c, TC_ERR_UNSUPPORTED, "band k-points are built for TC mode with one spin channel and no symmetry");
+  for (int b = 0; b < pb.nkb; ++b)
+    if (!pb.bloaded[b]) return fail(c, TC_ERR_STATE, "orbitals of band k-point " + std::to_string(b) + " not loaded");
+  if (pb.div && (pb.mask & TC_T_CORR))
+    return fail(c, TC_ERR_UNSUPPORTED, "the band forms of the divergence corrections are not built: set div_correction = 0");
+  const int nkb = pb.nkb, nb = pb.bnb, npm = sh.bnpm;
+  // plane-wave data of the band k-points
+  std::vector<int> box(size_t(nkb) * npm, 0), tk(nkb);
+  std::vector<double> kg(size_t(nkb) * npm * 3, 0.0);
+  for (int b = 0; b < nkb; ++b) {
+    tk[b] = pb.nk + b;
+    for (int g = 0; g < pb.bnpw[b]; ++g) {
+      const int* m = &pb.bmiller[b][3 * g];
+      const int x = (m[0] % pb.N + pb.N) % pb.N, y = (m[1] % pb.N + pb.N) % pb.N, z = (m[2] % pb.N + pb.N) % pb.N;
+      box[size_t(b) * npm + g] = (z * pb.N + y) * pb.N + x;
+      for (int cc = 0; cc < 3; ++cc)
+        kg[(size_t(b) * npm + g) * 3 + cc] = (pb.bk[3 * b] + m[0]) * pb.B[cc] + (pb.bk[3 * b + 1] + m[1]) * pb.B[3 + cc] +
+                                             (pb.bk[3 * b + 2] + m[2]) * pb.B[6 + cc];
+    }
+  }
+  sh.bbox.alloc(box.size());
+  sh.bkg.alloc(kg.size());
+  sh.bnpwd.alloc(nkb);
+  sh.btk.alloc(nkb);
+  sh.bout.alloc(size_t(2) * nkb * nb * npm);
+  sh.beps.alloc(size_t(2) * nkb * nb);
+  TC_HIP(hipMemcpy(sh.bbox.p, box.data(), box.size() * sizeof(int), hipMemcpyHostToDevice));
+  TC_HIP(hipMemcpy(sh.bkg.p, kg.data(), kg.size() * sizeof(double), hipMemcpyHostToDevice));
+  TC_HIP(hipMemcpy(sh.bnpwd.p, pb.bnpw.data(), nkb * sizeof(int), hipMemcpyHostToDevice));
+  TC_HIP(hipMemcpy(sh.btk.p, tk.data(), nkb * sizeof(int), hipMemcpyHostToDevice));
+  alloc_shared(c);
+  TargetSet ts;
+  ts.coef = sh.bcoef.p;
+  ts.nvec = nb;
+  ts.out = sh.bout.p;
+  ts.nblk = nkb;
+  ts.tk = sh.btk.p;
+  ts.boxidx = sh.bbox.p;
+  ts.npw = sh.bnpwd.p;
+  ts.kg = sh.bkg.p;
+  ts.npm = npm;
+  ts.band = true;
+  double stage[6];
+  c->eng->prof = &c->prof;
+  c->eng->apply(c->stream, sh, pb, stage, &ts);
+  hipLaunchKernelGGL(k_orbital_eps, dim3(nkb * nb), dim3(256), 0, c->stream, sh.bcoef.p, sh.bcoef.p, sh.bout.p, sh.bkg.p,
+                     sh.bnpwd.p, nb, npm, sh.beps.p);
+  if (out_host)
+    TC_HIP(hipMemcpyAsync(out_host, sh.bout.p, size_t(2) * nkb * nb * npm * sizeof(double), hipMemcpyDeviceToHost,
+                          c->stream));
+  if (eps_host)
+    TC_HIP(hipMemcpyAsync(eps_host, sh.beps.p, size_t(2) * nkb * nb * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  TC_HIP(hipStreamSynchronize(c->stream));
+  return TC_OK;
+}
 
 // ------------------------------------------------------------------ crystal symmetry (host)
 // Integer inverse of a unimodular 3x3 matrix (row-major).
@@ -3106,6 +3277,7 @@ int tc_set_kmesh(tc_ctx* c, int n1, int n2, int n3) {
     pb.loaded_dn.assign(pb.nk, 0);
     pb.nb = 0;
     pb.nsym = 0;
+    pb.nkb = 0;   // band k-points are coded after the mesh ones
     c->tables_dirty = true;
     c->have_result = false;
     return TC_OK;
@@ -3219,6 +3391,22 @@ int tc_set_nspin(tc_ctx* c, int nspin) {
     c->have_result = false;
     return TC_OK;
   });
+}
+
+int tc_set_band_kpoints(tc_ctx* c, int nkb, const double* kfrac) {
+  return guard(c, [&]() -> int { return set_band_kpoints(c, nkb, kfrac); });
+}
+
+int tc_set_band_basis(tc_ctx* c, int ib, int npw, const int32_t* miller) {
+  return guard(c, [&]() -> int { return set_band_basis(c, ib, npw, miller); });
+}
+
+int tc_load_band_orbitals(tc_ctx* c, int ib, int nband, const double* coef, const double* occ) {
+  return guard(c, [&]() -> int { return load_band_orbitals(c, ib, nband, coef, occ); });
+}
+
+int tc_apply_band(tc_ctx* c, double* out, double* eps) {
+  return guard(c, [&]() -> int { return do_apply_band(c, out, eps); });
 }
 
 int tc_set_symmetry(tc_ctx* c, int nsym, const int32_t* rot, const double* tau) {

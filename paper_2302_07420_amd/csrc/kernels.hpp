@@ -26,6 +26,7 @@ struct MeshInfo {
   int P;            // orbitals of one spin channel (nk * nb)
   int nbt;          // vectors per k-point of the target set (nb when the targets are the orbitals)
   const int* tk = nullptr;   // k-point of target block j / nbt (device; null: the block index itself)
+  int nkb = 0;               // band k-points, coded nk .. nk + nkb - 1 in tk
 };
 
 __device__ __forceinline__ int kindex_delta(const MeshInfo& mi, int kto, int kfrom) {
@@ -327,6 +328,11 @@ struct FusedArgs {
 // target jt sits at k-point jt / nbt, partner q at q / nb
 __device__ __forceinline__ int pair_dindex(const MeshInfo& mi, int jt, int q, int sign) {
   const int kt = mi.tk ? mi.tk[jt / mi.nbt] : jt / mi.nbt, kq = q / mi.nb;
+  const int nkm = mi.n1 * mi.n2 * mi.n3;
+  if (kt >= nkm) {   // band k-point: its own tables after the mesh differences, Delta = k_b - k_q then k_q - k_b
+    const int nd = (2 * mi.n1 - 1) * (2 * mi.n2 - 1) * (2 * mi.n3 - 1);
+    return nd + (sign ? 0 : mi.nkb * nkm) + (kt - nkm) * nkm + kq;
+  }
   return sign ? kindex_delta(mi, kt, kq) : kindex_delta(mi, kq, kt);
 }
 

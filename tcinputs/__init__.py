@@ -97,6 +97,11 @@ class Workload:
     right_dn: Optional[List[np.ndarray]] = None
     left_dn: Optional[List[np.ndarray]] = None
     occ_dn: Optional[List[np.ndarray]] = None
+    # band (zero-weight) k-points off the mesh: fractional k, plane waves, orbitals and fillings
+    band_k: Optional[np.ndarray] = None
+    band_miller: Optional[List[np.ndarray]] = None
+    band_right: Optional[List[np.ndarray]] = None
+    band_occ: Optional[List[np.ndarray]] = None
 
     @property
     def omega(self) -> float:
@@ -343,6 +348,34 @@ def sym_arrays(ops):
     rot = np.ascontiguousarray(np.stack([R for R, _ in ops]).astype(np.int32))
     tau = np.ascontiguousarray(np.stack([np.asarray(t, dtype=np.float64) for _, t in ops]))
     return rot, tau
+
+
+def with_band(w, kpoints, seed=None, source=None, shift=None, nb=None, ecut=None, occ=None):
+    """Adds band k-points (fractional, any position) to a workload.  Orbitals: with ``source`` (a mesh
+    k index per band k-point) the source k-point's coefficients on its own plane-wave set, shifted by the
+    integer vector ``shift`` (m -> m - shift, for k = k_source + shift + small offset); otherwise random
+    smooth orthonormal orbitals (seeded) on the sphere |k + G|^2 / 2 <= ecut.  Fillings ``occ`` per band
+    (default: those of the source, or 1)."""
+    kpoints = np.asarray(kpoints, dtype=np.float64).reshape(-1, 3)
+    B = reciprocal(w.lattice)
+    rng = np.random.Generator(np.random.PCG64(SEED_BASE + 900 if seed is None else seed))
+    mill, right, occs = [], [], []
+    for i, kf in enumerate(kpoints):
+        if source is not None:
+            s0 = source[i]
+            sh = np.zeros(3, dtype=np.int32) if shift is None else np.asarray(shift[i], dtype=np.int32)
+            mill.append((np.asarray(w.miller[s0]) - sh[None, :]).astype(np.int32))
+            right.append(np.array(w.right[s0], dtype=np.complex128))
+            occs.append(np.asarray(w.occ[s0] if occ is None else occ, dtype=np.float64).copy())
+        else:
+            M = miller_sphere(w.lattice, kf, ecut)
+            G = (M + kf[None, :]) @ B
+            env = np.exp(-np.sum(G * G, axis=1) / (2.0 * (3.0 * 2.0 * math.pi / 10.26) ** 2))
+            n = w.nband if nb is None else nb
+            mill.append(M)
+            right.append(_orthonormal_random(rng, M.shape[0], n, env))
+            occs.append(np.ones(n) if occ is None else np.asarray(occ, dtype=np.float64))
+    return w.replace(band_k=kpoints, band_miller=mill, band_right=right, band_occ=occs)
 
 
 def grid_fits(miller_list, grid) -> bool:
