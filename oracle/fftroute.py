@@ -31,7 +31,20 @@ Readings where the paper is silent or garbled (each restated in the design doc):
   R3  The 1/Omega carried by FT[chi* phi](0) is kept in every divergence
       correction (the paper's equations drop Omega factors, Sec. 2.6.1).
   R4  In the G = G' = 0 corrections of 3a2 and 3b6 the short-range part of u
-      enters once, as printed (Eqs. divcor_3a2_first and 3b6_div_scf1).
+      enters twice: the finite Q -> 0 remainder of Q^2 u~(Q)^2 =
+      (4 pi A / Q^2 + u~_short)(4 pi A + Q^2 u~_short) is 2 (4 pi A) u~_short(0);
+      Eqs. divcor_3a2_first and 3b6_div_scf1 keep one of the two cross terms.
+      Pinned by the band form (Eq. 3b6_div_band1, no u~_short): on the electron gas
+      the band-k operator tends to the mesh operator as k approaches a mesh point only
+      with this value.
+  R13 For a band k-point the vector sum of Eq. correction_nabla is taken at the
+      arguments k - q + G of the kernel it replaces (printed with q + G, which is zero
+      on the mesh).
+  R14 Band corrections of 3a4 and 3b5: the GB replacement is applied to the sums of
+      Algs. 3a4 and 3b5 as computed, whose two i factors give i^2 = -1; the prefactors
+      printed in Eqs. div_corr_3a4 and 3b5_div drop it (opposite sign).  With the
+      printed sign the 1/delta divergence at k -> a mesh point doubles instead of
+      cancelling.
   R5  Alg. 3b4 accumulates h2 * phi_q2 (the printed h3 <- h3 + h3 phi is a typo).
   R6  3a1 uses the bilinear h1 . h1 (printed |h1|^2; equal in TC mode).
   R7  The three-body total is 3a1 + 3a2 + 2 3a3 + 2 3a4 + 2 (3b1+...+3b6)
@@ -299,6 +312,20 @@ class Problem:
         self.gb_vector = vec / self.nk
         self.delta_gb = self.omega / (4.0 * math.sqrt(math.pi ** 3 * a)) - (-a + tot) / self.nk
 
+    def is_band(self, j):
+        return self.orb[0]["k"][j] >= self.nk
+
+    def band_set(self, s, j):
+        """Band target j: its k-point's orbitals (q_k of the band forms), the GB quantities there and
+        4 pi A_par (the parallel channel of the exchange-type terms)."""
+        ik = self.orb[s]["k"][j]
+        dgb, V = self.gb_band(ik)
+        return self.sel(s, ik), dgb, torch.as_tensor(V, dtype=RD), FOURPI * self.A[0]
+
+    def vdot(self, V, X):
+        """V . X over the leading vector axis of X (V Cartesian, real)."""
+        return sum(V[c] * X[c] for c in range(3))
+
     def gb_band(self, ik):
         """GB quantities at a band k-point (off the mesh, so no k - q + G vanishes): the bracket of
         Eq. correction with the mesh sum S = sum_{q,G} A_aux(k - q + G), divided by 4 pi as delta_gb is,
@@ -429,7 +456,24 @@ class Problem:
             rho = torch.conj(o["chi"][q])[None] * o["phi"][J]
             h = self.conv(d, "X", 0, self.FT(rho), "U")
             return -torch.sum(h * o["D"][q][None], 1) * o["w"][q]
-        return self._exchange_loop(s, body)
+        g = self._exchange_loop(s, body)
+        if self.div and self.nkb:
+            g = g + self._band_corr(s, self.c_2bx1_band)
+        return g
+
+    def _band_corr(self, s, fn):
+        """Stack fn(s, j) over the band targets (zeros elsewhere)."""
+        o = self.orb[s]
+        zero = torch.zeros_like(o["phi"][0])
+        return torch.stack([fn(s, j) if (self.is_band(j) and self.is_target(j)) else zero for j in range(self.P)])
+
+    def c_2bx1_band(self, s, j):
+        """Eq. divcorr_2bx1 (band k): i 4 pi A V . sum_mu f rho~_{mu j}(0) (nabla + ik) phi_mu."""
+        o = self.orb[s]
+        Q, _, V, a4 = self.band_set(s, j)
+        r0 = self.rho0(torch.conj(o["chi"][Q]), o["phi"][j][None])
+        DV = sum(V[c] * o["D"][Q][:, c] for c in range(3))
+        return 1j * a4 * torch.sum((o["f"][Q] * r0)[:, None, None, None] * DV, 0)
 
     def t_2bx2(self, s):
         """2bx2: +sum_q w [iQu~ . (*) chi_q^* (nabla+ik) phi_j] phi_q (grad_2 u_21 = -grad_1 u_12)."""
@@ -439,7 +483,18 @@ class Problem:
             rho = torch.conj(o["chi"][q])[None, None] * o["D"][J]
             h = -self.conv(d, "X", 0, self.FT(rho), "Ud")
             return h * o["phi"][q][None] * o["w"][q]
-        return self._exchange_loop(s, body)
+        g = self._exchange_loop(s, body)
+        if self.div and self.nkb:
+            g = g + self._band_corr(s, self.c_2bx2_band)
+        return g
+
+    def c_2bx2_band(self, s, j):
+        """Eq. divcorr_2bx2 (band k): -i 4 pi A sum_mu f (V . FT[chi_mu^* (nabla+ik) phi_j](0)) phi_mu."""
+        o = self.orb[s]
+        Q, _, V, a4 = self.band_set(s, j)
+        x = torch.mean(torch.conj(o["chi"][Q])[:, None] * o["D"][j][None], dim=(-3, -2, -1))   # (nq, 3)
+        c = torch.sum(x * V[None, :], 1)
+        return -1j * a4 * torch.sum((o["f"][Q] * c)[:, None, None, None] * o["phi"][Q], 0)
 
     # ---------------------------------------------------------------- three-body
     def h1(self, s):
@@ -470,7 +525,7 @@ class Problem:
         o2 = self.orb[s2]
         A, C = self.A[ch], self.C[ch]
         ushort = -FOURPI * A * C * C                                   # Eq. u_short
-        c1 = FOURPI * A * (FOURPI * A * self.delta_gb + ushort / self.nk)
+        c1 = FOURPI * A * (FOURPI * A * self.delta_gb + 2.0 * ushort / self.nk)   # reading R4
         _, _, utH = self.kern(np.zeros(3), "H", ch)
         out = 0
         for q1 in self.sel(s2, o2["k"][q2]):
@@ -498,6 +553,12 @@ class Problem:
             d = self.dk(o["k"][j], o["k"][q1])
             h3 = self.conv(d, "X", 0, self.FT(torch.conj(o["chi"][q1]) * o["phi"][j]), "U")
             h4 = h4 + h3 * o["phi"][q1][None] * o["w"][q1]
+        if self.div and self.is_band(j):
+            # Eq. divcorr_3a3 (= Eq. div_corr_3b4_2): -i 4 pi A V sum_mu f rho~_{mu j}(0) phi_mu
+            Q, _, V, a4 = self.band_set(s, j)
+            r0 = self.rho0(torch.conj(o["chi"][Q]), o["phi"][j][None])
+            p = torch.sum((o["f"][Q] * r0)[:, None, None, None] * o["phi"][Q], 0)
+            h4 = h4 + (-1j * a4) * V[:, None, None, None] * p[None]
         return h4
 
     def t_3a3(self, s):
@@ -530,6 +591,23 @@ class Problem:
                 d = self.dk(kt, o["k"][q2])
                 h5 = self.conv(d, "X", 0, self.FT(torch.conj(o["chi"][q2])[None] * o["phi"][J]), "U")
                 g[J] = g[J] - 0.5 * torch.sum(h3[None] * h5, 1) * o["w"][q2]
+        if self.div and self.nkb:
+            def corr(s_, j):
+                # the q2 sum of the algorithm at q2 -> k (Eq. div_corr_3a4_2) and the q1 sum inside h3 of
+                # the band orbitals (Eq. div_corr_3a4_3), with the algorithm's i^2 = -1 kept (reading R14):
+                #   +(i/2) 4 pi A sum_mu2 f rho~_{mu2 j}(0) V . h3(mu2)
+                #   +(1/2) (4 pi A)^2 V.V sum_{mu1 mu2} f f rho~_{mu1 mu2}(0) rho~_{mu2 j}(0) phi_mu1
+                Q, _, V, a4 = self.band_set(s_, j)
+                f = o["f"][Q]
+                r0 = self.rho0(torch.conj(o["chi"][Q]), o["phi"][j][None])                    # (nq,)
+                out = 0
+                for i2, m2 in enumerate(Q):
+                    out = out + 0.5j * a4 * f[i2] * r0[i2] * self.vdot(V, self.h3_3a4(s_, m2))
+                S = self.rho0(torch.conj(o["chi"][Q])[:, None], o["phi"][Q][None])              # (nq, nq)
+                cvec = (S * (f * r0)[None, :]).sum(1) * f                                         # over mu2
+                out = out + 0.5 * a4 * a4 * float(V @ V) * torch.sum(cvec[:, None, None, None] * o["phi"][Q], 0)
+                return out
+            g = g + self._band_corr(s, corr)
         return g
 
     def t_3b1(self, s):
@@ -570,7 +648,17 @@ class Problem:
             h2 = h1[None] * (torch.conj(o["chi"][q])[None] * o["phi"][J])[:, None]
             h3 = self.conv(d, "X", 0, self.FT(h2), "Ud")
             return 0.5 * h3 * o["phi"][q][None] * o["w"][q]
-        return self._exchange_loop(s, body)
+        g = self._exchange_loop(s, body)
+        if self.div and self.nkb:
+            def corr(s_, j):
+                # Eq. div_corr_3b3_2: (i/2) 4 pi A sum_mu f (V . FT[chi_mu^* phi_j h1](0)) phi_mu
+                Q, _, V, a4 = self.band_set(s_, j)
+                x = torch.mean(torch.conj(o["chi"][Q])[:, None] * (o["phi"][j][None] * h1)[None],
+                               dim=(-3, -2, -1))
+                c = torch.sum(x * V[None, :], 1)
+                return 0.5j * a4 * torch.sum((o["f"][Q] * c)[:, None, None, None] * o["phi"][Q], 0)
+            g = g + self._band_corr(s, corr)
+        return g
 
     def t_3b4(self, s):
         """Alg. 3b4 (with reading R5)."""
@@ -587,6 +675,12 @@ class Problem:
                 h4 = h3 * torch.conj(o["chi"][q1])[None]
                 h5 = self.conv(d, "X", 0, self.FT(h4), "Ud")
                 acc = acc - 0.5 * h5 * o["phi"][q1] * o["w"][q1]
+            if self.div and self.is_band(j):
+                # Eq. div_corr_3b4_4: -(i/2) 4 pi A sum_mu f (V . FT[chi_mu^* h3](0)) phi_mu
+                Q, _, V, a4 = self.band_set(s, j)
+                x = torch.mean(torch.conj(o["chi"][Q])[:, None] * h3[None], dim=(-3, -2, -1))   # (nq, 3)
+                c = torch.sum(x * V[None, :], 1)
+                acc = acc - 0.5j * a4 * torch.sum((o["f"][Q] * c)[:, None, None, None] * o["phi"][Q], 0)
             g.append(acc)
         return torch.stack(g)
 
@@ -604,6 +698,24 @@ class Problem:
                 h4 = h3[None] * o["phi"][J][:, None]
                 h5 = self.conv(d, "X", 0, self.FT(h4), "Ud")
                 g[J] = g[J] - 0.5 * h5 * o["phi"][q2][None] * o["w"][q2]
+        if self.div and self.nkb:
+            def corr(s_, j):
+                # the q2 sum at q2 -> k (Eq. 3b5_div_2) and the q1 sum inside h3 of the band orbitals
+                # (Eq. 3b5_div_3), signs from the algorithm (reading R14):
+                #   -(i/2) 4 pi A sum_mu2 f (V . FT[h3(mu2) phi_j](0)) phi_mu2
+                #   +(1/2) (4 pi A)^2 V.V sum_{mu1 mu2} f f rho~_{mu2 mu1}(0) rho~_{mu1 j}(0) phi_mu2
+                Q, _, V, a4 = self.band_set(s_, j)
+                f = o["f"][Q]
+                out = 0
+                for i2, m2 in enumerate(Q):
+                    x = torch.mean(self.h3_3b2(s_, m2) * o["phi"][j][None], dim=(-3, -2, -1))   # (3,)
+                    out = out - 0.5j * a4 * f[i2] * torch.sum(x * V) * o["phi"][m2]
+                S = self.rho0(torch.conj(o["chi"][Q])[:, None], o["phi"][Q][None])              # S[mu2, mu1]
+                r0 = self.rho0(torch.conj(o["chi"][Q]), o["phi"][j][None])                    # rho~_{mu1 j}
+                cvec = (S * (f * r0)[None, :]).sum(1) * f                                         # per mu2
+                out = out + 0.5 * a4 * a4 * float(V @ V) * torch.sum(cvec[:, None, None, None] * o["phi"][Q], 0)
+                return out
+            g = g + self._band_corr(s, corr)
         return g
 
     def t_3b6(self, s):
@@ -634,20 +746,36 @@ class Problem:
                 continue
             Q = self.sel(s, o["k"][j])
             acc = 0
+            band = self.is_band(j)
+            if band:
+                dgb_b, V = self.gb_band(o["k"][j])
+                V = torch.as_tensor(V, dtype=RD)
+                Gc = self.qvec(np.zeros(3))                                     # Cartesian G (N1,N2,N3,3)
+                VG = torch.sum(Gc * V, -1)
             for s1 in range(2):
                 ch = _pair(s1, s)
                 A, C = self.A[ch], self.C[ch]
-                ushort = -FOURPI * A * C * C
-                c1 = 2.0 * math.pi * A * (FOURPI * A * self.delta_gb + ushort / self.nk)
                 _, _, utH = self.kern(np.zeros(3), "H", ch)
                 nG = self.nG[s1]
-                field = self.IFT(utH * nG)
+                if not band:
+                    ushort = -FOURPI * A * C * C
+                    c1 = 2.0 * math.pi * A * (FOURPI * A * self.delta_gb + 2.0 * ushort / self.nk)   # R4
+                    field = self.IFT(utH * nG)
+                else:
+                    # Eqs. 3b6_div_band1-3: band GB bracket without alpha and u_short; the G' != 0 and
+                    # G + G' = 0 parts through the vector sum of Eq. correction_nabla
+                    c1 = 2.0 * math.pi * A * FOURPI * A * dgb_b
+                    field = -2.0 * math.pi * A * self.IFT(VG * utH * nG)
                 for q2 in Q:
                     rG = self.FT(torch.conj(o["chi"][q2]) * o["phi"][j])
                     r0 = rG[0, 0, 0]
                     t1 = c1 * r0 * nG[0, 0, 0]
-                    t3 = 2.0 * math.pi * A / self.nk * torch.sum(utH * rG * self.neg(nG))
-                    t2 = 2.0 * math.pi * A / self.nk * r0 * field
+                    if not band:
+                        t3 = 2.0 * math.pi * A / self.nk * torch.sum(utH * rG * self.neg(nG))
+                        t2 = 2.0 * math.pi * A / self.nk * r0 * field
+                    else:
+                        t3 = -2.0 * math.pi * A * torch.sum(VG * utH * rG * self.neg(nG))
+                        t2 = r0 * field
                     acc = acc + o["f"][q2] * (t1 + t3 + t2) * o["phi"][q2]
             out.append(acc)
         return torch.stack(out)

@@ -115,7 +115,7 @@ def heg_terms(w, A=None, C=None, alpha=None, div_correction=True):
     for s in (0, 1):                 # channel of (target spin, spin of q1 and q2)
         h5 = (wq[:, None] * Dn2 * ut[s] ** 2 * off).sum(0) / omega ** 2     # index q2 (sum over q1)
         if div_correction:
-            c1 = FOURPI * A[s] * (FOURPI * A[s] * dgb + ushort[s] / nk)
+            c1 = FOURPI * A[s] * (FOURPI * A[s] * dgb + 2.0 * ushort[s] / nk)   # reading R4
             h5 = h5 + c1 * f / omega ** 2
         h6 += np.sum(wq * h5)
     eps["3a2"] = np.full(P, 0.5 * h6)
@@ -131,7 +131,7 @@ def heg_terms(w, A=None, C=None, alpha=None, div_correction=True):
     for s in (0, 1):                # channel of (spin of the density, target spin)
         b6 = b6 + 0.5 * (wq[None, :] * Dn2 * ut[s] ** 2 * off).sum(1) * nbar / omega
         if div_correction:
-            c1 = 2.0 * math.pi * A[s] * (FOURPI * A[s] * dgb + ushort[s] / nk)
+            c1 = 2.0 * math.pi * A[s] * (FOURPI * A[s] * dgb + 2.0 * ushort[s] / nk)   # reading R4
             b6 = b6 + c1 * (1.0 / omega) * nbar * f
     eps["3b6"] = b6
     return eps, p, f

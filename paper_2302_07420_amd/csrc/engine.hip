@@ -986,12 +986,13 @@ struct EngineT : Engine {
     TC_HIP(hipMemcpy(tHu0.p, hu0.data(), NR * sizeof(double), hipMemcpyHostToDevice));
     TC_HIP(hipMemcpy(tHu1.p, hu1.data(), NR * sizeof(double), hipMemcpyHostToDevice));
     // correction prefactors: A (Eqs. divcor_3a2_second, 3b6_div_scf2/3) and
-    // A [4 pi A Delta_GB + u~_short(0)/N_k] with u~_short(0) = -4 pi A C^2 (Eqs. u_short, divcor_3a2_first,
-    // 3b6_div_scf1)
+    // A [4 pi A Delta_GB + 2 u~_short(0)/N_k] with u~_short(0) = -4 pi A C^2 (Eqs. u_short, divcor_3a2_first,
+    // 3b6_div_scf1).  The factor 2: the finite Q -> 0 remainder of Q^2 u~(Q)^2 holds both cross terms of
+    // (4 pi A/Q^2 + u~_short)(4 pi A + Q^2 u~_short).
     for (int ch = 0; ch < 2; ++ch) {
       corrA[ch] = chan_eval(tv, pb.A, pb.C, ch, [](auto A, auto) { return A; });
       corrB[ch] = chan_eval(tv, pb.A, pb.C, ch, [&](auto A, auto C) {
-        return A * (kFourPi * A * pb.delta_gb - kFourPi * A * C * C / double(pb.nk));
+        return A * (kFourPi * A * pb.delta_gb - 2.0 * kFourPi * A * C * C / double(pb.nk));
       });
     }
   }
