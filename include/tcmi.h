@@ -175,10 +175,13 @@ int tc_load_band_orbitals(tc_ctx* ctx, int ib, int nband, const double* coef, co
 /* Apply the two- and three-body operator of the loaded mesh orbitals (Eq. SCF with the selected terms) to
  * every band orbital: out (host, may be NULL) receives [nkb][nband][npw_max_band] complex128 (H c)(G) on
  * each band k-point's plane waves, zero-padded; eps (host, may be NULL) [nkb][nband] complex128 orbital
- * energies <phi| T + h |phi>.  The shift of each pair is k_b - k_q exactly (no reduction modulo G).  The
- * band forms of the divergence corrections are not built: with div_correction set and the correction
- * bit selected this returns TC_ERR_UNSUPPORTED.  TC mode, one spin channel, no symmetry
- * (TC_ERR_UNSUPPORTED otherwise). */
+ * energies <phi| T + h |phi>.  The shift of each pair is k_b - k_q exactly (no reduction modulo G).  With
+ * div_correction set and the correction bit selected, the band forms of the divergence corrections are
+ * applied (Eqs. divcorr_2ax_band, divcorr_2bx1/2, divcorr_3a3, div_corr_3a4_2/3, div_corr_3b3_2,
+ * div_corr_3b4_2/4, 3b5_div_2/3, 3b6_div_band1-3, with the band k-point's own orbitals and fillings as the
+ * orbitals q_k at the singular point, and the corrections of the occupied rows' h5 of Alg. 3a2); a band
+ * k-point on the mesh (modulo G) is then TC_ERR_ARG (use the mesh k-point).  TC mode, one spin channel, no
+ * symmetry (TC_ERR_UNSUPPORTED otherwise). */
 int tc_apply_band(tc_ctx* ctx, double* out, double* eps);
 
 /* Crystal symmetry (Sec. 2.6.1: the orbital of k = R^T k0 - b is the image of that of k0; Sec. 2.6.4: the

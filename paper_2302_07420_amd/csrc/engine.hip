@@ -13,6 +13,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <complex>
 #include <cstdio>
 #include <cstring>
 #include <memory>
@@ -25,6 +26,7 @@
 #include "../../include/tcmi.h"
 #include "kernels.hpp"
 #include "sym.hpp"
+#include "band.hpp"
 #include "scf.hpp"
 
 using namespace tcmi;
@@ -283,6 +285,7 @@ struct Shared {                       // precision-independent device data
   DBuf<double> outI, epartI;            // [nirr nb][npw_max] complex, [nirr nb][kAccSlots]
   // band k-points: coefficients [nkb][bnb][bnpm] (complex128), plane-wave data, k codes, output, energies
   DBuf<double> bcoef, bkg, bout, beps;
+  DBuf<double> bdh4, bV, bOBh4, bOB3, bZ5, bOB6, bW4, bX6, bWa;   // band corrections
   DBuf<int> bbox, bnpwd, btk;
   int bnpm = 0;
 };
@@ -767,6 +770,18 @@ struct TargetSet {
   const double* kg = nullptr;
   int npm = 0;
   bool band = false;
+  // band divergence corrections (null: off): device a-coefficients of the h4 correction [NTG][nvec]
+  // complex, V of each band k-point [nblk][3], and the outputs of the grid pieces
+  const double* bdh4 = nullptr;
+  const double* bV = nullptr;
+  double* OBh4 = nullptr;   // [NTG][nvec][3] complex: <psi_mu | h4_j> / N^3 (corrected h4)
+  double* OB3 = nullptr;    // [NTG][nvec][3] complex: <psi_mu | psi_j h1_c> / N^3
+  double* Z5 = nullptr;     // [NTG][nvec][3] complex: <H3B_mu,c | psi_j> / N^3 (H3 of the band rows)
+  double* OB6 = nullptr;    // [NTG][nvec] complex: <psi_mu | F3b6 psi_j> / N^3
+  double* W4 = nullptr;     // [NTG][npm] complex: (V . H3B_j)(G) on the band plane waves
+  double* X6 = nullptr;     // [NTG][npm] complex: (F3b6 psi_j)(G)
+  double* Wa = nullptr;     // [NTG][npm] complex: (F2 psi_j)(G), the 3a2 field of the occupied set
+  double c3b6[2] = {0, 0};  // -2 pi A_ch, the 3b6 band-field prefactors per channel
 };
 
 struct Engine {
@@ -1319,6 +1334,25 @@ struct EngineT : Engine {
     });
     TC_HIP(hipEventRecord(ev.e[3], s));
 
+    // band divergence corrections: h3 of the band orbitals as rows of the occupied-occupied pass
+    // (partners: the mesh orbitals; Delta = k_q - k_b), needed by the band forms of 3a4 and 3b5
+    if (ts && ts->OBh4) {
+      H3I.alloc(size_t(3) * NTG * NR);
+      h5I.alloc(size_t(NTG) * NR);
+      for (int a0 = 0; a0 < NTG; a0 += T) {
+        const int nt = std::min(T, NTG - a0);
+        const long npair = long(nt) * P;
+        const FusedArgs fa{P, nt, a0, S, chunk};
+        hipLaunchKernelGGL((k_pair_xy<R, N, true>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, tP, psi.p, fa,
+                           bufA.p);
+        zconv<OP_O>(s, npair, a0, miT, tb, 0);
+        hipLaunchKernelGGL((k_fused_O<R, N>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, bufB.p, psi.p, sh.w.p, fa,
+                           miT, rc, dfr.p, h5part.p, H3part.p);
+        hipLaunchKernelGGL((k_sum_parts<R, N>), dim3(nblk(long(nt) * NR)), dim3(256), 0, s, 0, S, nt, a0, 0,
+                           h5part.p, H3part.p, nullptr, nullptr, h5I.p, H3I.p, nullptr, nullptr);
+      }
+    }
+
     // ---- 3/4: target batches (pass A, pass B, local terms, r -> G)
     const bool need_A = m.m2ax || m.m2bx1 || m.m2bx2 || m.m3a3 || m.m3a4 || m.m3b4 || m.m3b6;
     const bool need_B = m.m2bx2 || m.m3b3 || m.m3b4 || m.m3b5;
@@ -1353,6 +1387,12 @@ struct EngineT : Engine {
           hipLaunchKernelGGL((k_sum_parts<R, N>), dim3(nblk(long(nt) * NR)), dim3(256), 0, s, 1, S, nt, t0, 0, nullptr,
                              nullptr, gpart.p, h4part.p, nullptr, nullptr, acc.p, h4.p);
         });
+        if (ts && ts->bdh4) {   // band k-points: h4 of Alg. 3a3 (h3 of Alg. 3b4) corrected at q1 -> k, then <psi_mu|h4_j>
+          hipLaunchKernelGGL((k_band_dh4<R, N>), dim3(nblk(long(nt) * NR)), dim3(256), 0, s, tP, ts->bdh4, ts->bV, t0,
+                             nt, nbt, h4.p);
+          hipLaunchKernelGGL((k_band_dot<R, R, R>), dim3(nt * nbt * 3), dim3(256), 0, s, tP, NR, 0L, h4.p, 3 * NR, NR,
+                             t0, (const cx<R>*)nullptr, 0L, t0, nbt, 3, NR, ts->OBh4);
+        }
         if (m.m3b6) {
           K(TC_K_ZCONV_A2, fb * 5.0 * npair + tabB, [&] {
             zconv<OP_A2>(s, npair, t0, miT, tb, 1);
@@ -1403,6 +1443,7 @@ struct EngineT : Engine {
                            t0, nt, 1.0 / double(NR), ts ? ts->out : sh.out.p, NR);
       });
     }
+    if (ts && ts->OBh4) band_grid(s, sh, pb, *ts, NTG, tP, tbox, tnpw, tkg, tnpm, rc);
     TC_HIP(hipEventRecord(ev.e[4], s));
 
     // ---- 5: kinetic energy and FP64 corrections
@@ -1433,6 +1474,71 @@ struct EngineT : Engine {
     stage_ms[3] = msA;
     stage_ms[4] = msB;
     stage_ms[5] = ev.ms(3, 5) - msA - msB;
+  }
+
+  // Grid pieces of the band corrections (see band.hpp and do_apply_band): <psi_mu|psi_j h1>, <H3B_mu|psi_j>,
+  // (V . H3B_j)(G); in FP64 the 3a2 field F2 of the occupied set applied to the band orbitals and the 3b6
+  // band field with its products and means.
+  void band_grid(hipStream_t s, Shared& sh, const Problem& pb, const TargetSet& ts, int NTG, const cx<R>* tP,
+                 const int* tbox, const int* tnpw, const double* tkg, int tnpm, const Recip& rc) {
+    const int nb = ts.nvec, nkb = ts.nblk, P = pb.P(), nk = pb.nk, npm = pb.npw_max;
+    // 3b3: <psi_mu | psi_j h1_c> (h1: Cartesian, loc + N^3)
+    hipLaunchKernelGGL((k_band_dot<R, R, R>), dim3(NTG * nb * 3), dim3(256), 0, s, tP, NR, 0L, tP, NR, 0L, 0,
+                       (const cx<R>*)(loc.p + NR), NR, 0, nb, 3, NR, ts.OB3);
+    // 3b5: <H3B_mu,c | psi_j>; 3a4: (V . H3B_j)(G)
+    hipLaunchKernelGGL((k_band_dot<R, R, R>), dim3(NTG * nb * 3), dim3(256), 0, s, H3I.p, 3 * NR, NR, tP, NR, 0L, 0,
+                       (const cx<R>*)nullptr, 0L, 0, nb, 3, NR, ts.Z5);
+    g.alloc(size_t(std::max(T, NTG)) * NR);
+    hipLaunchKernelGGL((k_band_vdot<R, N>), dim3(nblk(long(NTG) * NR)), dim3(256), 0, s, H3I.p, ts.bV, NTG, nb, g.p);
+    fft3d_t<R, N>(g.p, NTG, -1, s);
+    hipLaunchKernelGGL((k_gather<R>), dim3(nblk(long(NTG) * tnpm)), dim3(256), 0, s, g.p, tbox, tnpw, nb, tnpm, 0, NTG,
+                       1.0 / double(NR), ts.W4, NR);
+    // FP64: mesh orbitals, n~, the Y source and F2 of 3a2 (as in corrections())
+    TC_HIP(hipMemsetAsync(psi64.p, 0, size_t(P) * NR * sizeof(cx<double>), s));
+    hipLaunchKernelGGL((k_scatter<double>), dim3(nblk(long(P) * npm)), dim3(256), 0, s, sh.coef.p, sh.boxidx.p,
+                       sh.npw.p, sh.kg.p, pb.nb, npm, P, -1, psi64.p, NR);
+    fft3d_t<double, N>(psi64.p, P, +1, s);
+    hipLaunchKernelGGL(k_overlap, dim3(nk * pb.nb * pb.nb), dim3(256), 0, s, sh.coef.p, pb.nb, sh.coef.p, pb.nb,
+                       sh.npw.p, npm, nk, sh.S.p);
+    std::vector<double> fo(pb.occ);
+    focc.alloc(P);
+    TC_HIP(hipMemcpyAsync(focc.p, fo.data(), P * sizeof(double), hipMemcpyHostToDevice, s));
+    cx<double>* nG = v64.p;
+    cx<double>* YG = v64.p + NR;
+    cx<double>* F2 = v64.p + 2 * NR;
+    cx<double>* F6 = v64.p + 3 * NR;
+    hipLaunchKernelGGL((k_density64<N>), dim3(nblk(NR)), dim3(256), 0, s, psi64.p, psi64.p, sh.w.p, P, nG);
+    hipLaunchKernelGGL((k_corr_Ysrc<N>), dim3(nblk(NR)), dim3(256), 0, s, psi64.p, psi64.p, sh.S.p, focc.p, nk, pb.nb,
+                       1.0 / (nk * pb.omega), YG);
+    fft3d_t<double, N>(nG, 2, -1, s);
+    const double a0 = 2 * kPi * corrA[0] / nk, a1 = 2 * kPi * corrA[1] / nk;
+    hipLaunchKernelGGL((k_corr_gfields<N>), dim3(nblk(NR)), dim3(256), 0, s, tHu0.p, tHu1.p, 2 * a0, 2 * a1, YG, F2);
+    fft3d_t<double, N>(F2, 1, +1, s);
+    // band orbitals in FP64
+    psiT64.alloc(size_t(NTG) * NR);
+    prodT.alloc(size_t(2) * NTG * NR);
+    TC_HIP(hipMemsetAsync(psiT64.p, 0, size_t(NTG) * NR * sizeof(cx<double>), s));
+    hipLaunchKernelGGL((k_scatter<double>), dim3(nblk(long(NTG) * tnpm)), dim3(256), 0, s, ts.coef, tbox, tnpw, tkg,
+                       nb, tnpm, NTG, -1, psiT64.p, NR);
+    fft3d_t<double, N>(psiT64.p, NTG, +1, s);
+    // 3a2 on the band targets: (F2 psi_j)(G)
+    hipLaunchKernelGGL((k_band_mul<N>), dim3(nblk(long(NTG) * NR)), dim3(256), 0, s, F2, psiT64.p, NTG, prodT.p);
+    fft3d_t<double, N>(prodT.p, NTG, -1, s);
+    hipLaunchKernelGGL((k_gather<double>), dim3(nblk(long(NTG) * tnpm)), dim3(256), 0, s, prodT.p, tbox, tnpw, nb,
+                       tnpm, 0, NTG, 1.0 / double(NR), ts.Wa, NR);
+    // 3b6 band field of each band k-point, its products with the band orbitals and the means
+    for (int b = 0; b < nkb; ++b) {
+      hipLaunchKernelGGL((k_band_f3b6<N>), dim3(nblk(NR)), dim3(256), 0, s, rc, tHu0.p, tHu1.p, ts.c3b6[0], ts.c3b6[1],
+                         ts.bV + 3 * b, nG, F6);
+      fft3d_t<double, N>(F6, 1, +1, s);
+      hipLaunchKernelGGL((k_band_mul<N>), dim3(nblk(long(nb) * NR)), dim3(256), 0, s, F6, psiT64.p + size_t(b) * nb * NR,
+                         nb, prodT.p + size_t(b) * nb * NR);
+      hipLaunchKernelGGL((k_band_dot<double, double, double>), dim3(nb * nb), dim3(256), 0, s, psiT64.p, NR, 0L,
+                         prodT.p, NR, 0L, 0, (const cx<double>*)nullptr, 0L, b * nb, nb, 1, NR, ts.OB6);
+    }
+    fft3d_t<double, N>(prodT.p, NTG, -1, s);
+    hipLaunchKernelGGL((k_gather<double>), dim3(nblk(long(NTG) * tnpm)), dim3(256), 0, s, prodT.p, tbox, tnpw, nb,
+                       tnpm, 0, NTG, 1.0 / double(NR), ts.X6, NR);
   }
 
   // Application with crystal symmetry (TC mode, one spin channel): the occupied-occupied rows (q2 of
@@ -2302,6 +2408,168 @@ int load_band_orbitals(tc_ctx* c, int ib, int nband, const double* coef, const d
   return TC_OK;
 }
 
+// GB quantities at band k-point kf (off the mesh, no vanishing argument): Delta_GB^band =
+// Omega / (4 sqrt(pi^3 alpha)) - (1/N_k) sum_{q,G} A_aux(k - q + G) (Eq. divcorr_2ax_band, divided by 4 pi)
+// and V = (1/N_k) sum_{q,G} (k - q + G) A_aux(k - q + G) (Cartesian; the vector sum of Eq. correction_nabla at
+// the arguments of the kernel it replaces).  False when some k - q + G vanishes (k on the mesh).
+bool gb_band(const Problem& pb, const double* kf, double& dgb, double* V) {
+  const double a = pb.alpha;
+  const double qmax = std::sqrt(41.45 / a);
+  int mm[3];
+  for (int i = 0; i < 3; ++i) {
+    const double L = std::sqrt(pb.lat[3 * i] * pb.lat[3 * i] + pb.lat[3 * i + 1] * pb.lat[3 * i + 1] +
+                               pb.lat[3 * i + 2] * pb.lat[3 * i + 2]);
+    mm[i] = int(std::ceil(qmax * L / (2 * kPi))) + 3;
+  }
+  double sum = 0, comp = 0, v[3] = {0, 0, 0};
+  for (int ik = 0; ik < pb.nk; ++ik) {
+    double f[3];
+    pb.kfrac(ik, f);
+    for (int m1 = -mm[0]; m1 <= mm[0]; ++m1)
+      for (int m2 = -mm[1]; m2 <= mm[1]; ++m2)
+        for (int m3 = -mm[2]; m3 <= mm[2]; ++m3) {
+          const double c1 = m1 + kf[0] - f[0], c2 = m2 + kf[1] - f[1], c3 = m3 + kf[2] - f[2];
+          double Q[3];
+          for (int cc = 0; cc < 3; ++cc) Q[cc] = c1 * pb.B[cc] + c2 * pb.B[3 + cc] + c3 * pb.B[6 + cc];
+          const double q2 = Q[0] * Q[0] + Q[1] * Q[1] + Q[2] * Q[2];
+          if (q2 < 1e-16) return false;
+          if (a * q2 >= 41.45) continue;
+          const double t = std::exp(-a * q2) / q2;
+          const double y = t - comp, z = sum + y;   // Kahan
+          comp = (z - sum) - y;
+          sum = z;
+          for (int cc = 0; cc < 3; ++cc) v[cc] += Q[cc] * t;
+        }
+  }
+  dgb = pb.omega / (4.0 * std::sqrt(kPi * kPi * kPi * a)) - sum / pb.nk;
+  for (int cc = 0; cc < 3; ++cc) V[cc] = v[cc] / pb.nk;
+  return true;
+}
+
+// Band forms of the divergence corrections, combined in FP64 on the host (coefficients on each band
+// k-point's plane waves; psi = sqrt(Omega) phi, rho~_{mu j}(0) = S_mu,j / Omega; the multiplicities of the
+// three-body terms are those of the operator).  Singular exchange sums at Delta = k - q get the GB
+// replacement of Eq. correction (Delta_GB^band) or Eq. correction_nabla (V) with the band k-point's own
+// orbitals mu (fillings f_mu):
+//   2ax  (Eq. divcorr_2ax_band):  -4 pi Dgb sum f rho c_mu
+//   2bx1 (Eq. divcorr_2bx1):      -4 pi A sum f rho (V . (k+G)) c_mu
+//   2bx2 (Eq. divcorr_2bx2):      -i 4 pi A sum f (V . X_mu,j) c_mu,   X = (i/Omega) sum conj(c_mu)(k+G) c_j
+//   3a3, 3b4 (h4 correction, Eqs. divcorr_3a3, div_corr_3b4_2): on the device before pass B
+//   3b4  (Eq. div_corr_3b4_4):    2 x -(i/2) 4 pi A sum f (V . <psi_mu|h4_j>/Omega) c_mu
+//   3b3  (Eq. div_corr_3b3_2):    2 x (i/2) 4 pi A sum f (V . <psi_mu|psi_j h1>/Omega) c_mu
+//   3a4  (Eqs. div_corr_3a4_2/3, reading R14): 2 x [(i/2) 4 pi A sum f rho_mu2,j (V . H3_mu2)(G)
+//                                      + (1/2)(4 pi A)^2 V.V sum f f rho_mu1,mu2 rho_mu2,j c_mu1]
+//   3b5  (Eqs. 3b5_div_2/3, R14): 2 x [-(i/2) 4 pi A sum f (V . <H3_mu2|psi_j>/Omega) c_mu2
+//                                      + (1/2)(4 pi A)^2 V.V sum f f rho_mu2,mu1 rho_mu1,j c_mu2]
+//   3b6  (Eqs. 3b6_div_band1-3):  2 x sum f [c1b n0 rho c_mu + rho (F psi_mu)(G) - <psi_mu|F psi_j>/Omega c_mu]
+//   3a2  (the corrections of the mesh rows' h5, Eqs. divcor_3a2_first/second): (1/2)(const1 c_j + (F2 psi_j)(G))
+void band_corrections_host(tc_ctx* c, const Masks& m, const std::vector<double>& cb,
+                           const std::vector<std::complex<double>>& Sb, const std::vector<double>& dgbb,
+                           const std::vector<double>& Vb, std::vector<double>& out) {
+  using zc = std::complex<double>;
+  Problem& pb = c->pb;
+  Shared& sh = c->sh;
+  const int nkb = pb.nkb, nb = pb.bnb, npm = sh.bnpm, NTG = nkb * nb;
+  const double Om = pb.omega, a4 = kFourPi * pb.A[0];
+  auto rd = [&](DBuf<double>& d, size_t n) {
+    std::vector<double> h(n);
+    TC_HIP(hipMemcpy(h.data(), d.p, n * sizeof(double), hipMemcpyDeviceToHost));
+    return h;
+  };
+  const auto OBh4 = rd(sh.bOBh4, size_t(2) * NTG * nb * 3), OB3 = rd(sh.bOB3, size_t(2) * NTG * nb * 3);
+  const auto Z5 = rd(sh.bZ5, size_t(2) * NTG * nb * 3), OB6 = rd(sh.bOB6, size_t(2) * NTG * nb);
+  const auto W4 = rd(sh.bW4, size_t(2) * NTG * npm), X6 = rd(sh.bX6, size_t(2) * NTG * npm);
+  const auto Wa = rd(sh.bWa, size_t(2) * NTG * npm);
+  auto z = [](const std::vector<double>& v, size_t i) { return zc(v[2 * i], v[2 * i + 1]); };
+  auto C = [&](int j, int g) { return zc(cb[2 * (size_t(j) * npm + g)], cb[2 * (size_t(j) * npm + g) + 1]); };
+  // mesh side: per-spin n~(0) and const1 of the 3a2 correction (as in the corrections of the mesh targets)
+  const int P = pb.P(), pnpm = pb.npw_max;
+  std::vector<double> cm(size_t(2) * P * pnpm);
+  TC_HIP(hipMemcpy(cm.data(), sh.coef.p, cm.size() * sizeof(double), hipMemcpyDeviceToHost));
+  auto Cm = [&](int j, int g) { return zc(cm[2 * (size_t(j) * pnpm + g)], cm[2 * (size_t(j) * pnpm + g) + 1]); };
+  double n0 = 0, cs = 0;
+  for (int k = 0; k < pb.nk; ++k) {
+    std::vector<zc> S(size_t(pb.nb) * pb.nb);
+    for (int a = 0; a < pb.nb; ++a)
+      for (int b = 0; b < pb.nb; ++b) {
+        zc sacc = 0;
+        for (int g = 0; g < pb.npw[k]; ++g) sacc += std::conj(Cm(k * pb.nb + a, g)) * Cm(k * pb.nb + b, g);
+        S[size_t(a) * pb.nb + b] = sacc;
+      }
+    for (int a = 0; a < pb.nb; ++a) {
+      const double fa = pb.occ[size_t(k) * pb.nb + a];
+      n0 += fa / pb.nk * S[size_t(a) * pb.nb + a].real() / Om;
+      for (int b = 0; b < pb.nb; ++b)
+        cs += fa / pb.nk * pb.occ[size_t(k) * pb.nb + b] * (S[size_t(a) * pb.nb + b] * S[size_t(b) * pb.nb + a]).real() /
+              (Om * Om);
+    }
+  }
+  double c1a = 0, c1b_unit = 0;
+  for (int ch = 0; ch < 2; ++ch) {
+    const double A = pb.A[ch], Cc = pb.C[ch];
+    c1a += kFourPi * A * (kFourPi * A * pb.delta_gb - 2.0 * kFourPi * A * Cc * Cc / pb.nk);   // reading R4
+    c1b_unit += 2.0 * kPi * A * kFourPi * A;   // times Delta_GB^band (Eq. 3b6_div_band1)
+  }
+  const double const1 = c1a * cs;
+  for (int j = 0; j < NTG; ++j) {
+    const int b = j / nb, q0 = b * nb;
+    const double* V = &Vb[3 * b];
+    const double VV = V[0] * V[0] + V[1] * V[1] + V[2] * V[2];
+    auto f = [&](int mu) { return pb.bocc[size_t(b) * nb + mu]; };
+    auto rho = [&](int mu, int jj) { return Sb[size_t(jj) * nb + mu] / Om; };   // <c_mu|c_jj> / Omega
+    // per-mu coefficients of c_mu(G) and of (V . (k+G)) c_mu(G)
+    std::vector<zc> al(nb, 0.0), be(nb, 0.0), ga(nb, 0.0), de(nb, 0.0);
+    for (int mu = 0; mu < nb; ++mu) {
+      const int qm = q0 + mu;
+      const zc r = rho(mu, j);
+      al[mu] += m.m2ax * (-kFourPi * dgbb[b]) * f(mu) * r;
+      be[mu] += m.m2bx1 * (-a4) * f(mu) * r;
+      zc X[3] = {0, 0, 0};
+      for (int g = 0; g < pb.bnpw[b]; ++g) {
+        const int* mi = &pb.bmiller[b][3 * g];
+        const zc w = std::conj(C(qm, g)) * C(j, g);
+        for (int cc = 0; cc < 3; ++cc)
+          X[cc] += w * ((pb.bk[3 * b] + mi[0]) * pb.B[cc] + (pb.bk[3 * b + 1] + mi[1]) * pb.B[3 + cc] +
+                        (pb.bk[3 * b + 2] + mi[2]) * pb.B[6 + cc]);
+      }
+      zc VX = 0, Vh4 = 0, V3 = 0, V5 = 0;
+      for (int cc = 0; cc < 3; ++cc) {
+        VX += V[cc] * X[cc] * zc(0, 1) / Om;
+        Vh4 += V[cc] * z(OBh4, (size_t(j) * nb + mu) * 3 + cc) / Om;
+        V3 += V[cc] * z(OB3, (size_t(j) * nb + mu) * 3 + cc) / Om;
+        V5 += V[cc] * z(Z5, (size_t(j) * nb + mu) * 3 + cc) / Om;
+      }
+      al[mu] += m.m2bx2 * zc(0, -a4) * f(mu) * VX;
+      al[mu] += 2.0 * m.m3b4 * zc(0, -0.5 * a4) * f(mu) * Vh4;
+      al[mu] += 2.0 * m.m3b3 * zc(0, 0.5 * a4) * f(mu) * V3;
+      ga[mu] += 2.0 * m.m3a4 * zc(0, 0.5 * a4) * f(mu) * r;                   // times (V . H3_mu)(G)
+      al[mu] += 2.0 * m.m3b5 * zc(0, -0.5 * a4) * f(mu) * V5;
+      de[mu] += 2.0 * m.m3b6 * f(mu) * r;                                      // times (F psi_mu)(G)
+      al[mu] += 2.0 * m.m3b6 * f(mu) * (c1b_unit * dgbb[b] * n0 * r - z(OB6, size_t(j) * nb + mu) / Om);
+      for (int m2 = 0; m2 < nb; ++m2) {
+        // 3a4: mu plays mu1; 3b5: mu plays mu2 (partner index m2 plays mu1)
+        al[mu] += 2.0 * m.m3a4 * 0.5 * a4 * a4 * VV * f(mu) * f(m2) * rho(mu, q0 + m2) * rho(m2, j);
+        al[mu] += 2.0 * m.m3b5 * 0.5 * a4 * a4 * VV * f(mu) * f(m2) * rho(mu, q0 + m2) * rho(m2, j);
+      }
+    }
+    for (int g = 0; g < pb.bnpw[b]; ++g) {
+      const int* mi = &pb.bmiller[b][3 * g];
+      double vk = 0;
+      for (int cc = 0; cc < 3; ++cc)
+        vk += V[cc] * ((pb.bk[3 * b] + mi[0]) * pb.B[cc] + (pb.bk[3 * b + 1] + mi[1]) * pb.B[3 + cc] +
+                       (pb.bk[3 * b + 2] + mi[2]) * pb.B[6 + cc]);
+      zc acc = m.m3a2 * 0.5 * (const1 * C(j, g) + z(Wa, size_t(j) * npm + g));
+      for (int mu = 0; mu < nb; ++mu) {
+        const int qm = q0 + mu;
+        acc += (al[mu] + be[mu] * vk) * C(qm, g) + ga[mu] * z(W4, size_t(qm) * npm + g) +
+               de[mu] * z(X6, size_t(qm) * npm + g);
+      }
+      out[2 * (size_t(j) * npm + g)] += acc.real();
+      out[2 * (size_t(j) * npm + g) + 1] += acc.imag();
+    }
+  }
+}
+
 // The operator of the loaded (mesh) orbitals applied to the orbitals of the band k-points, and their
 // orbital energies.
 int do_apply_band(tc_ctx* c, double* out_host, double* eps_host) {
@@ -2314,9 +2582,27 @@ int do_apply_band(tc_ctx* c, double* out_host, double* eps_host) {
     return fail(c, TC_ERR_UNSUPPORTED, "band k-points are built for TC mode with one spin channel and no symmetry");
   for (int b = 0; b < pb.nkb; ++b)
     if (!pb.bloaded[b]) return fail(c, TC_ERR_STATE, "orbitals of band k-point " + std::to_string(b) + " not loaded");
-  if (pb.div && (pb.mask & TC_T_CORR))
-    return fail(c, TC_ERR_UNSUPPORTED, "the band forms of the divergence corrections are not built: set div_correction = 0");
+  const bool corr = pb.div && (pb.mask & TC_T_CORR);
   const int nkb = pb.nkb, nb = pb.bnb, npm = sh.bnpm;
+  const int NTG = nkb * nb;
+  // band GB quantities and the band orbitals' overlaps (FP64, host)
+  std::vector<double> dgbb(nkb), Vb(size_t(3) * nkb);
+  for (int b = 0; b < nkb; ++b)
+    if (corr && !gb_band(pb, &pb.bk[3 * b], dgbb[b], &Vb[3 * b]))
+      return fail(c, TC_ERR_ARG, "band k-point " + std::to_string(b) + " lies on the mesh: use the mesh k-point");
+  std::vector<double> cb(size_t(2) * NTG * npm);
+  TC_HIP(hipMemcpy(cb.data(), sh.bcoef.p, cb.size() * sizeof(double), hipMemcpyDeviceToHost));
+  const double a4 = kFourPi * pb.A[0];   // 4 pi A of the parallel channel (exchange-type terms)
+  using zc = std::complex<double>;
+  auto coef = [&](int j, int g) { return zc(cb[2 * (size_t(j) * npm + g)], cb[2 * (size_t(j) * npm + g) + 1]); };
+  std::vector<zc> Sb(size_t(NTG) * nb);   // Sb[j][mu] = <c_mu|c_j> (mu, j at the same band k-point)
+  for (int j = 0; j < NTG; ++j)
+    for (int mu = 0; mu < nb; ++mu) {
+      const int b = j / nb, q = b * nb + mu;
+      zc sacc = 0;
+      for (int g = 0; g < pb.bnpw[b]; ++g) sacc += std::conj(coef(q, g)) * coef(j, g);
+      Sb[size_t(j) * nb + mu] = sacc;
+    }
   // plane-wave data of the band k-points
   std::vector<int> box(size_t(nkb) * npm, 0), tk(nkb);
   std::vector<double> kg(size_t(nkb) * npm * 3, 0.0);
@@ -2353,17 +2639,63 @@ int do_apply_band(tc_ctx* c, double* out_host, double* eps_host) {
   ts.kg = sh.bkg.p;
   ts.npm = npm;
   ts.band = true;
+  const Masks m = make_masks(pb.mask);
+  if (corr) {
+    // h4 correction coefficients a[j][mu] = -i 4 pi A f_mu S_mu,j / Omega (Eqs. divcorr_3a3, div_corr_3b4_2)
+    std::vector<double> ah(size_t(2) * NTG * nb);
+    for (int j = 0; j < NTG; ++j)
+      for (int mu = 0; mu < nb; ++mu) {
+        const zc v = zc(0, -a4) * pb.bocc[size_t(j / nb) * nb + mu] * Sb[size_t(j) * nb + mu] / pb.omega;
+        ah[2 * (size_t(j) * nb + mu)] = v.real();
+        ah[2 * (size_t(j) * nb + mu) + 1] = v.imag();
+      }
+    sh.bdh4.alloc(ah.size());
+    sh.bV.alloc(Vb.size());
+    TC_HIP(hipMemcpy(sh.bdh4.p, ah.data(), ah.size() * sizeof(double), hipMemcpyHostToDevice));
+    TC_HIP(hipMemcpy(sh.bV.p, Vb.data(), Vb.size() * sizeof(double), hipMemcpyHostToDevice));
+    for (auto* x : {&sh.bOBh4, &sh.bOB3, &sh.bZ5}) x->alloc(size_t(2) * NTG * nb * 3);
+    sh.bOB6.alloc(size_t(2) * NTG * nb);
+    for (auto* x : {&sh.bW4, &sh.bX6, &sh.bWa}) x->alloc(size_t(2) * NTG * npm);
+    ts.bdh4 = sh.bdh4.p;
+    ts.bV = sh.bV.p;
+    ts.OBh4 = sh.bOBh4.p;
+    ts.OB3 = sh.bOB3.p;
+    ts.Z5 = sh.bZ5.p;
+    ts.OB6 = sh.bOB6.p;
+    ts.W4 = sh.bW4.p;
+    ts.X6 = sh.bX6.p;
+    ts.Wa = sh.bWa.p;
+    ts.c3b6[0] = -2.0 * kPi * pb.A[0];
+    ts.c3b6[1] = -2.0 * kPi * pb.A[1];
+  }
   double stage[6];
   c->eng->prof = &c->prof;
   c->eng->apply(c->stream, sh, pb, stage, &ts);
-  hipLaunchKernelGGL(k_orbital_eps, dim3(nkb * nb), dim3(256), 0, c->stream, sh.bcoef.p, sh.bcoef.p, sh.bout.p, sh.bkg.p,
-                     sh.bnpwd.p, nb, npm, sh.beps.p);
-  if (out_host)
-    TC_HIP(hipMemcpyAsync(out_host, sh.bout.p, size_t(2) * nkb * nb * npm * sizeof(double), hipMemcpyDeviceToHost,
-                          c->stream));
-  if (eps_host)
-    TC_HIP(hipMemcpyAsync(eps_host, sh.beps.p, size_t(2) * nkb * nb * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  std::vector<double> out(size_t(2) * NTG * npm);
+  TC_HIP(hipMemcpyAsync(out.data(), sh.bout.p, out.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
   TC_HIP(hipStreamSynchronize(c->stream));
+  if (corr) band_corrections_host(c, m, cb, Sb, dgbb, Vb, out);
+  // orbital energies <phi| T + h |phi> (FP64, host)
+  std::vector<double> eps(size_t(2) * NTG);
+  for (int j = 0; j < NTG; ++j) {
+    const int b = j / nb;
+    zc e = 0;
+    for (int g = 0; g < pb.bnpw[b]; ++g) {
+      const int* mi = &pb.bmiller[b][3 * g];
+      double kg2 = 0;
+      for (int cc = 0; cc < 3; ++cc) {
+        const double q = (pb.bk[3 * b] + mi[0]) * pb.B[cc] + (pb.bk[3 * b + 1] + mi[1]) * pb.B[3 + cc] +
+                         (pb.bk[3 * b + 2] + mi[2]) * pb.B[6 + cc];
+        kg2 += q * q;
+      }
+      const zc cj = coef(j, g), hc(out[2 * (size_t(j) * npm + g)], out[2 * (size_t(j) * npm + g) + 1]);
+      e += std::conj(cj) * (0.5 * kg2 * cj + hc);
+    }
+    eps[2 * j] = e.real();
+    eps[2 * j + 1] = e.imag();
+  }
+  if (out_host) std::memcpy(out_host, out.data(), out.size() * sizeof(double));
+  if (eps_host) std::memcpy(eps_host, eps.data(), eps.size() * sizeof(double));
   return TC_OK;
 }
 

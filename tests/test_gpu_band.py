@@ -1,7 +1,8 @@
-"""Band (zero-weight) k-points off the SCF mesh through the C ABI (tc_apply_band), corrections off.
+"""Band (zero-weight) k-points off the SCF mesh through the C ABI (tc_apply_band).
 
 Against the FP64 oracle, whose band orbitals are targets of every term and partners of none: every term
-and the total on random off-mesh k-points (FP64), the total and the orbital energies in FP32.
+and the total on random off-mesh k-points (FP64), the total and the orbital energies in FP32, without and
+with the band forms of the divergence corrections.
 Independent of the oracle: a band k-point placed on a mesh k-point with that k-point's orbitals gives the
 mesh result, also when shifted by a reciprocal lattice vector with its plane waves shifted back.
 """
@@ -47,24 +48,27 @@ CASES = {
 }
 
 
-@pytest.fixture(scope="module", params=list(CASES))
+@pytest.fixture(scope="module", params=[(c, d) for c in CASES for d in (False, True)],
+                ids=[f"{c}-{'corr' if d else 'nocorr'}" for c in CASES for d in (False, True)])
 def case(request):
-    w = CASES[request.param]()
-    pr = Problem(w, div_correction=False)
+    name, div = request.param
+    w = CASES[name]()
+    pr = Problem(w, div_correction=div)
     nk = w.nk
     per = {t: [c.numpy() for c in pr.to_coeff(MULT.get(t, 1) * pr.term(t, 0))][nk:] for t in ALL_TERMS}
     tot = [sum(per[t][b] for t in ALL_TERMS) for b in range(len(w.band_k))]
     g = sum(MULT.get(t, 1) * pr.term(t, 0) for t in ALL_TERMS)
     eps = pr.braket(0, g).numpy()[pr.Pm:].reshape(len(w.band_k), -1) + _band_kinetic(w)
-    return request.param, w, per, tot, eps
+    return f"{name}-{'corr' if div else 'nocorr'}", div, w, per, tot, eps
 
 
 def test_every_term_fp64(case):
-    name, w, per, tot, eps = case
+    name, div, w, per, tot, eps = case
     scale = max(np.abs(x).max() for x in tot)
     for t in ALL_TERMS:
         _say(f"[gpu] band {name} fp64 term {t}")
-        op = tc.from_workload(w, precision=tc.TC_PREC_FP64, terms=tc.TERM_BITS[t], div_correction=False)
+        op = tc.from_workload(w, precision=tc.TC_PREC_FP64, terms=tc.TERM_BITS[t] | tc.TERM_BITS["corr"],
+                              div_correction=div)
         got, _ = op.apply_band()
         op.close()
         err = max(np.abs(g - r).max() for g, r in zip(got, per[t])) / scale
@@ -73,9 +77,9 @@ def test_every_term_fp64(case):
 
 @pytest.mark.parametrize("prec,tol", [("fp64", FP64_TOL), ("fp32", FP32_TOL)])
 def test_total_and_orbital_energies(case, prec, tol):
-    name, w, per, tot, eps = case
+    name, div, w, per, tot, eps = case
     _say(f"[gpu] band {name} {prec} total")
-    op = tc.from_workload(w, precision=tc.TC_PREC_FP64 if prec == "fp64" else tc.TC_PREC_FP32, div_correction=False)
+    op = tc.from_workload(w, precision=tc.TC_PREC_FP64 if prec == "fp64" else tc.TC_PREC_FP32, div_correction=div)
     got, eg = op.apply_band()
     op.close()
     err = relerr(got, tot)
@@ -104,8 +108,11 @@ def test_band_point_on_the_mesh_and_shifted():
 def test_band_rejections():
     w = CASES["fcc_k211_g8_band3"]()
     _say("[gpu] band: rejections")
-    op = tc.from_workload(w, precision=tc.TC_PREC_FP64, div_correction=True)
-    with pytest.raises(tc.TCError, match="band forms"):
+    # with corrections, a band k-point on the mesh (modulo G) is the mesh k-point
+    w0 = T.tiny_fcc(kmesh=(2, 1, 1), grid=8, ecut=2.0, nb=2, a=6.0, occ=[1.0, 0.7])
+    wm = T.with_band(w0, [w0.kfrac[1] + np.array([0.0, 1.0, 0.0])], source=[1], shift=[[0, 1, 0]])
+    op = tc.from_workload(wm, precision=tc.TC_PREC_FP64, div_correction=True)
+    with pytest.raises(tc.TCError, match="on the mesh"):
         op.apply_band()
     op.close()
     op = tc.from_workload(w.replace(band_k=None), precision=tc.TC_PREC_FP64, div_correction=False)
