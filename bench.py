@@ -165,6 +165,7 @@ def main():
     ap.add_argument("--no-bitc", action="store_true", help="skip the biorthogonal-mode side measurement")
     ap.add_argument("--no-scf", action="store_true", help="skip the block-Davidson SCF side measurement")
     ap.add_argument("--no-sym", action="store_true", help="skip the crystal-symmetry side measurement")
+    ap.add_argument("--no-band", action="store_true", help="skip the band k-point side measurement")
     ap.add_argument("--workload", default="fcc_si_k444_g24",
                     help="named workload: fcc_si_k444_g24 (default), heg14_g16, heg54_twist2_g32, fcc_si_x2_k222_g48")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
@@ -278,6 +279,37 @@ def main():
                "energy_rel_err_vs_unreduced_fp64": abs(e_y - res_y["full_fp64"][1]) / abs(res_y["full_fp64"][1])}
         log(f"symmetry fp32: {ms_y:.2f} ms/step vs unreduced {res_y['full_fp32'][0]:.2f} ms/step, E = {e_y:.12f}")
 
+    band = None
+    if not args.no_band and args.workload == "fcc_si_k444_g24":
+        # band structure: the operator of the mesh orbitals applied to 4 orbitals at each of 16 k-points on
+        # L - Gamma - X (off the mesh), with the band forms of the divergence corrections; one application
+        # includes the mesh densities and occupied-occupied pass
+        import numpy as np
+
+        wb = T.workload("fcc_si_k444_g24_band16")
+        res_b = {}
+        for name, prec, nst in (("fp32", tc.TC_PREC_FP32, max(1, min(args.steps, 3))), ("fp64", tc.TC_PREC_FP64, 1)):
+            op_b, keep_b = make_op(wb, prec, stream)
+            op_b.set_band(wb.band_k, wb.band_miller, wb.band_right, wb.band_occ)
+            op_b.apply_band()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(nst):
+                _, eps_b = op_b.apply_band()
+            torch.cuda.synchronize()
+            res_b[name] = ((time.perf_counter() - t0) / nst * 1e3, eps_b)
+            op_b.close()
+            del keep_b
+        nbp = len(wb.band_k) * wb.band_right[0].shape[0] * wb.nk * wb.nband
+        e32, e64 = res_b["fp32"][1], res_b["fp64"][1]
+        band = {"workload": wb.name, "band_kpoints": len(wb.band_k), "orbitals_per_kpoint": wb.band_right[0].shape[0],
+                "ms_per_application": res_b["fp32"][0], "fp64_ms_per_application": res_b["fp64"][0],
+                "band_pairs_per_s": nbp / (res_b["fp32"][0] / 1e3),
+                "band_energy_max_abs_err_fp32_vs_fp64_Ha": float(np.max(np.abs(e32 - e64))),
+                "band_energies_fp64_Ha": [[float(x.real) for x in row] for row in e64]}
+        log(f"band: {res_b['fp32'][0]:.1f} ms per application (fp64 {res_b['fp64'][0]:.1f}), "
+            f"max |eps32 - eps64| = {band['band_energy_max_abs_err_fp32_vs_fp64_Ha']:.2e} Ha")
+
     # dominant kernel and its roofline (algorithmic bytes / event-timed duration)
     dom = max(stats.items(), key=lambda kv: kv[1]["ms"])
     name, st = dom
@@ -334,6 +366,7 @@ def main():
         "bitc_fp32_gpu": bitc,
         "scf_davidson_gpu": scf,
         "symmetry_fp32_gpu": sym,
+        "band_fp32_gpu": band,
         "stages_ms": dict(zip(tc.STAGES, stages)),
         "kernels_ms_per_step": per_kernel,
         "kernel_ms_per_step_total": total_kernel_ms,

@@ -459,7 +459,19 @@ WORKLOADS = {
     # the fcc bench shape with orbitals invariant under the diamond structure's 48 operations (8 of the
     # 64 k-points are representatives)
     "fcc_si_k444_g24_sym": lambda: symmetric_orbitals(fcc_si(), diamond_ops(fcc_lattice(10.26)), SEED_BASE + 44),
+    # the fcc bench shape with 16 band k-points on the path L - Gamma - X (none on the 4x4x4 mesh), four
+    # random smooth orbitals each on their own plane-wave sets
+    "fcc_si_k444_g24_band16": lambda: with_band(fcc_si(), band_path_fcc(), seed=SEED_BASE + 45, ecut=8.14, nb=4),
 }
+
+
+def band_path_fcc():
+    """16 fractional k-points on L - Gamma - X of the fcc reciprocal lattice (L = (1/2,1/2,1/2), X = (1/2,1/2,0)
+    in units of the reciprocal rows), avoiding the 4x4x4 mesh."""
+    L = np.array([0.5, 0.5, 0.5])
+    X = np.array([0.5, 0.5, 0.0])
+    s = [0.05, 0.17, 0.29, 0.41, 0.53, 0.65, 0.77, 0.89]
+    return np.array([L * (1.0 - t) for t in s] + [X * t for t in [0.11, 0.23, 0.37, 0.47, 0.61, 0.73, 0.83, 0.97]])
 
 
 def workload(name: str) -> Workload:
