@@ -185,6 +185,8 @@ struct Problem {
   int bnb = 0;                            // orbitals per band k-point
   std::vector<double> bocc;               // [nkb][bnb]
   std::vector<char> bloaded;
+  std::vector<double> bdgb, bVg;           // GB quantities per band k-point (cached for band_alpha)
+  double band_alpha = -1;
 
   int P() const { return nk * nb; }
   long NR() const { return long(N) * N * N; }
@@ -2359,6 +2361,7 @@ int set_band_kpoints(tc_ctx* c, int nkb, const double* kfrac) {
   pb.bnb = 0;
   pb.bocc.clear();
   pb.bloaded.assign(nkb, 0);
+  pb.band_alpha = -1;
   c->tables_dirty = true;   // band shift tables
   return TC_OK;
 }
@@ -2586,10 +2589,16 @@ int do_apply_band(tc_ctx* c, double* out_host, double* eps_host) {
   const int nkb = pb.nkb, nb = pb.bnb, npm = sh.bnpm;
   const int NTG = nkb * nb;
   // band GB quantities and the band orbitals' overlaps (FP64, host)
-  std::vector<double> dgbb(nkb), Vb(size_t(3) * nkb);
-  for (int b = 0; b < nkb; ++b)
-    if (corr && !gb_band(pb, &pb.bk[3 * b], dgbb[b], &Vb[3 * b]))
-      return fail(c, TC_ERR_ARG, "band k-point " + std::to_string(b) + " lies on the mesh: use the mesh k-point");
+  if (corr && pb.band_alpha != pb.alpha) {   // the GB sums depend on the cell, mesh, alpha and band k-points
+    pb.bdgb.assign(nkb, 0.0);
+    pb.bVg.assign(size_t(3) * nkb, 0.0);
+    for (int b = 0; b < nkb; ++b)
+      if (!gb_band(pb, &pb.bk[3 * b], pb.bdgb[b], &pb.bVg[3 * b]))
+        return fail(c, TC_ERR_ARG, "band k-point " + std::to_string(b) + " lies on the mesh: use the mesh k-point");
+    pb.band_alpha = pb.alpha;
+  }
+  const std::vector<double> dgbb = corr ? pb.bdgb : std::vector<double>(nkb, 0.0);
+  const std::vector<double> Vb = corr ? pb.bVg : std::vector<double>(size_t(3) * nkb, 0.0);
   std::vector<double> cb(size_t(2) * NTG * npm);
   TC_HIP(hipMemcpy(cb.data(), sh.bcoef.p, cb.size() * sizeof(double), hipMemcpyDeviceToHost));
   const double a4 = kFourPi * pb.A[0];   // 4 pi A of the parallel channel (exchange-type terms)
@@ -3589,6 +3598,7 @@ int tc_set_cell(tc_ctx* c, const double lat[9]) {
       for (int k = 0; k < 3; ++k) pb.B[3 * j + k] = 2.0 * kPi * inv[3 * k + j];
     pb.cell = true;
     pb.nsym = 0;   // operations are stated for a given cell, k-mesh and grid
+    pb.band_alpha = -1;
     c->tables_dirty = true;
     c->have_result = false;
     return TC_OK;
