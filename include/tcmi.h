@@ -337,6 +337,17 @@ int tc_last_timing(tc_ctx* ctx, double* total_ms, double* stage_ms, int n);
  * buffers.  Results do not depend on it; tests use small values to cover batching. */
 int tc_set_batch(tc_ctx* ctx, int targets_per_batch);
 
+/* Resident pair store (on = 1, the default): when tc_apply_all* runs with the orbitals as targets
+ * and every pair's pass-A z-stage output (5 P^2 fields of N1 N2 N3 working-precision complex values)
+ * fits on the device with a quarter of its memory (at least 16 GiB) left free, those outputs are
+ * computed once and kept, and the occupied-occupied pass reads its four fields per pair from them
+ * (the pair (a, b) of that pass is the pass-A pair with target b and partner a: same density
+ * conj(psi_a) psi_b, same momentum k_b - k_a) instead of recomputing them.  Otherwise, and with
+ * on = 0, both passes transform their own pair densities.  Results do not depend on it; the store
+ * is released when it is switched off.  Biorthogonal mode, trial vectors, band k-points,
+ * symmetry-reduced and spin-polarised runs always use the batched form. */
+int tc_set_pair_store(tc_ctx* ctx, int on);
+
 /* Kernels timed by tc_kernel_stats (device time between HIP events recorded on the
  * context's stream around every launch).  Each index names one kernel symbol of the
  * library (working precision R, grid length N), as listed by a kernel trace. */

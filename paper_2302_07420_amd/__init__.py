@@ -90,6 +90,7 @@ def lib():
         "tc_sync": (I, [P]),
         "tc_last_timing": (I, [P, dp, dp, I]),
         "tc_set_batch": (I, [P, I]),
+        "tc_set_pair_store": (I, [P, I]),
         "tc_set_profiling": (I, [P, I]),
         "tc_kernel_stats": (I, [P, dp, dp, dp, I]),
     }
@@ -343,6 +344,9 @@ class TCOperator:
     def set_batch(self, targets_per_batch: int):
         self._check(self._L.tc_set_batch(self._h, int(targets_per_batch)), "tc_set_batch")
 
+    def set_pair_store(self, on: bool):
+        self._check(self._L.tc_set_pair_store(self._h, int(bool(on))), "tc_set_pair_store")
+
     def set_profiling(self, on: bool):
         self._check(self._L.tc_set_profiling(self._h, int(bool(on))), "tc_set_profiling")
 
@@ -360,12 +364,14 @@ class TCOperator:
 
 
 def from_workload(w, precision=TC_PREC_FP64, terms=TERM_ALL, div_correction=True, device=0, A=None, C=None,
-                  coeff=None, stream=None, batch=0, left=None, symmetry=None) -> TCOperator:
+                  coeff=None, stream=None, batch=0, left=None, symmetry=None, pair_store=True) -> TCOperator:
     """Build an operator from a ``tcinputs.Workload``: TC mode, or the biorthogonal mode when the workload
     (or ``left``) holds left orbitals; ``symmetry``: crystal operations [(R, tau)] (see set_symmetry)."""
     op = TCOperator(device, stream)
     if batch:
         op.set_batch(batch)
+    if not pair_store:
+        op.set_pair_store(False)
     op.set_cell(w.lattice)
     op.set_kmesh(*w.kmesh)
     op.set_grid(*w.grid)

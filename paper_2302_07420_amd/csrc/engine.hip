@@ -170,6 +170,7 @@ struct Problem {
   std::vector<char> loaded_dn;            // per k (nspin = 2)
   double delta_gb = 0, sigma_aux = 0;
   int batch = 0;                          // targets per batch (0 = automatic)
+  int pair_store = 1;                     // keep every pair's pass-A z-stage output resident when it fits
   // crystal symmetry (tc_set_symmetry): operations x -> R (x + tau) and the k-point orbits
   int nsym = 0;
   std::vector<int> symR;                  // [nsym][9]
@@ -841,6 +842,7 @@ struct EngineT : Engine {
   DBuf<R> h5;          // [P][NR]
   DBuf<cx<R>> bufA;    // [T*P][4][NR]  pair densities, 3b6 and pass-B sources
   DBuf<cx<R>> bufB;    // [T*P][5][NR]  z-stage outputs
+  DBuf<cx<R>> allB;    // [P*P][5][NR]  pass-A z-stage outputs of every pair (resident store)
   DBuf<cx<R>> h4, Z;   // [T][3][NR]  h4 (Cartesian), pass-B target factor (lattice)
   DBuf<cx<R>> g;       // [T][NR]
   DBuf<cx<double>> acc;     // [kAccSlots][T][NR]  FP64 accumulation of the operator output, per energy slot
@@ -1079,6 +1081,28 @@ struct EngineT : Engine {
     zconv<OP>(s, bufA.p, bufB.p, npair, t0, mi, tb, sign);
   }
 
+  // The resident store of pass-A z-stage outputs: allocated when it leaves a quarter of the device (at
+  // least 16 GiB) free, released when it does not fit.
+  bool pair_store(const Problem& pb) {
+    const size_t need = size_t(5) * pb.P() * pb.P() * NR;
+    if (!pb.pair_store) {
+      allB.release();
+      return false;
+    }
+    if (allB.n >= need) return true;
+    allB.release();
+    size_t fr = 0, tot = 0;
+    if (hipMemGetInfo(&fr, &tot) != hipSuccess) return false;
+    const size_t bytes = need * sizeof(cx<R>);
+    if (bytes + std::max<size_t>(tot / 4, size_t(16) << 30) > fr) return false;
+    try {
+      allB.alloc(need);
+    } catch (const TcError&) {
+      return false;
+    }
+    return true;
+  }
+
   void ensure(const Problem& pb, size_t budget_bytes) {
     const int P = pb.P();
     if (P == P_alloc && pb.batch == batch_alloc && pb.bitc == bitc_alloc && pb.nspin == nspin_alloc) return;
@@ -1263,7 +1287,28 @@ struct EngineT : Engine {
 
     // ---- 2: occupied-occupied pair pass (Algs. 3a2, 3a4 and 3b2/3b5 first loops)
     const bool need_occ = m.m3a2 || m.m3a4 || m.m3b2 || m.m3b5;
+    const bool need_A = m.m2ax || m.m2bx1 || m.m2bx2 || m.m3a3 || m.m3a4 || m.m3b4 || m.m3b6;
+    const bool need_B = m.m2bx2 || m.m3b3 || m.m3b4 || m.m3b5;
     const int chunk = (P + S - 1) / S;
+    // With the orbitals as targets, the pass-A pair (t = b, q = a) has the density conj(psi_a) psi_b and the
+    // momentum Delta = k_b - k_a of the occupied pair (a, b), and the four fields of its z stage after V are
+    // the occupied pass's.  When every pair's pass-A z-stage output fits on the device it is computed once,
+    // before the occupied pass, which then reads it in place of its own pair densities and z stage.
+    const bool keepA = !bitc && !ts && need_occ && need_A && pair_store(pb);
+    if (keepA) {
+      for (int t0 = 0; t0 < P; t0 += T) {
+        const int nt = std::min(T, P - t0);
+        const long npair = long(nt) * P;
+        const FusedArgs fa{P, nt, t0, S, chunk};
+        K(TC_K_XY_PAIR_TGT, fb * (npair + nt + P), [&] {
+          hipLaunchKernelGGL((k_pair_xy<R, N, false>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, X, psi.p, fa,
+                             bufA.p);
+        });
+        K(TC_K_ZCONV_A1, fb * 6.0 * npair + tabB, [&] {
+          zconv<OP_A1>(s, bufA.p, allB.p + size_t(t0) * P * 5 * NR, npair, t0, miT, tb, 1);
+        });
+      }
+    }
     TC_HIP(hipMemsetAsync(H3a4.p, 0, size_t(3) * P * NR * sizeof(cx<R>), s));
     if (bitc) TC_HIP(hipMemsetAsync(H3bc.p, 0, size_t(3) * P * NR * sizeof(cx<R>), s));
     if (need_occ) {
@@ -1271,7 +1316,18 @@ struct EngineT : Engine {
         const int nt = std::min(T, P - a0);
         const long npair = long(nt) * P;
         const FusedArgs fa{P, nt, a0, S, chunk};
-        if (!bitc) {
+        if (keepA) {
+          // row a = a0 + t, partner b = q: fields 1..4 of the stored pair b P + a
+          K(TC_K_FUSED_O, fb * (4.0 * npair + P) + 3.5 * fb * nt * S, [&] {
+            hipLaunchKernelGGL((k_fused_O<R, N>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s,
+                               allB.p + (size_t(a0) * 5 + 1) * NR, psi.p, sh.w.p, fa, mi, rc, dfr.p, h5part.p,
+                               H3part.p, 5L, 5L * P);
+          });
+          K(TC_K_SUM_PARTS, 4.0 * fb * nt * (S + 1), [&] {
+            hipLaunchKernelGGL((k_sum_parts<R, N>), dim3(nblk(long(nt) * NR)), dim3(256), 0, s, 0, S, nt, a0, 0,
+                               h5part.p, H3part.p, nullptr, nullptr, h5.p, H3a4.p, nullptr, nullptr);
+          });
+        } else if (!bitc) {
           K(TC_K_XY_PAIR_OCC, fb * (npair + nt + P), [&] {
             hipLaunchKernelGGL((k_pair_xy<R, N, true>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, psi.p, psi.p,
                                fa, bufA.p);
@@ -1356,8 +1412,6 @@ struct EngineT : Engine {
     }
 
     // ---- 3/4: target batches (pass A, pass B, local terms, r -> G)
-    const bool need_A = m.m2ax || m.m2bx1 || m.m2bx2 || m.m3a3 || m.m3a4 || m.m3b4 || m.m3b6;
-    const bool need_B = m.m2bx2 || m.m3b3 || m.m3b4 || m.m3b5;
     for (int t0 = 0; t0 < NTG; t0 += T) {
       const int nt = std::min(T, NTG - t0);
       const long npair = long(nt) * P;
@@ -1373,15 +1427,18 @@ struct EngineT : Engine {
       const double part = fb * nt * S;   // one working-precision field per (chunk, target)
       if (need_A) {
         const FusedArgs fa{P, nt, t0, S, chunk};
-        K(TC_K_XY_PAIR_TGT, fb * (npair + nt + P), [&] {
-          hipLaunchKernelGGL((k_pair_xy<R, N, false>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, X, tP, fa,
-                             bufA.p);
-        });
-        K(TC_K_ZCONV_A1, fb * 6.0 * npair + tabB, [&] {
-          zconv<OP_A1>(s, npair, t0, miT, tb, 1);
-        });
+        const cx<R>* zA = keepA ? allB.p + size_t(t0) * P * 5 * NR : bufB.p;
+        if (!keepA) {
+          K(TC_K_XY_PAIR_TGT, fb * (npair + nt + P), [&] {
+            hipLaunchKernelGGL((k_pair_xy<R, N, false>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, X, tP, fa,
+                               bufA.p);
+          });
+          K(TC_K_ZCONV_A1, fb * 6.0 * npair + tabB, [&] {
+            zconv<OP_A1>(s, npair, t0, miT, tb, 1);
+          });
+        }
         K(TC_K_FUSED_A, fb * ((m.m3b6 ? 9.0 : 5.0) * npair + 8.0 * P + nt) + 6.0 * part, [&] {
-          hipLaunchKernelGGL((k_fused_A<R, N>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, bufB.p, psi.p, Dl.p,
+          hipLaunchKernelGGL((k_fused_A<R, N>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, zA, psi.p, Dl.p,
                              Hl.p, nJ.p, sh.w.p, fa, m, int(m.m3b6 != 0), miT, bm, mm, dfr.p, bufA.p, gpart.p,
                              h4part.p);
         });
@@ -3925,6 +3982,14 @@ int tc_set_batch(tc_ctx* c, int targets_per_batch) {
   return guard(c, [&]() -> int {
     if (targets_per_batch < 0) return fail(c, TC_ERR_ARG, "batch must be >= 0");
     c->pb.batch = targets_per_batch;
+    c->have_result = false;
+    return TC_OK;
+  });
+}
+
+int tc_set_pair_store(tc_ctx* c, int on) {
+  return guard(c, [&]() -> int {
+    c->pb.pair_store = on != 0;
     c->have_result = false;
     return TC_OK;
   });

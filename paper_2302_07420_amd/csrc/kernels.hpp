@@ -1099,7 +1099,8 @@ __global__ void __launch_bounds__((Fz<R, N>::NTH)) k_fused_Y(const cx<R>* buf1, 
 }
 
 // Occupied-occupied pass: buf4 per pair (a = t0 + t, b = q; Delta = k_b - k_a), xy in G space:
-// [W0_par, W3_par, W0_anti, W3_anti].  With V_s the Cartesian vector fields:
+// [W0_par, W3_par, W0_anti, W3_anti] at field offset (t sT + q sQ) N^3 (sT < 0: the pair-major layout
+// sT = 4P, sQ = 4 of the pass's own z stage).  With V_s the Cartesian vector fields:
 //   h5[a]   += w_b (|V_par|^2 + |V_anti|^2)     (Alg. 3a2; TC mode: V_ba = conj(V_ab))
 //   H3a4[a] += w_b conj(V_par) psi_b            (Alg. 3a4 h3; Alg. 3b2 h3 is its conjugate)
 template <typename R, int N>
@@ -1114,10 +1115,11 @@ struct PassO {
 template <typename R, int N, bool SPLITH = false>
 __global__ void __launch_bounds__((Fz<R, N>::NTH)) k_fused_O(const cx<R>* buf4, const cx<R>* psi, const double* w,
                                                            FusedArgs fa, MeshInfo mi, Recip rc, const double* dfr,
-                                                           R* h5part, cx<R>* H3part) {
+                                                           R* h5part, cx<R>* H3part, long sT = -1, long sQ = 4) {
   using F = Fz<R, N>;
   constexpr int KP = F::KP, RB = F::RB, PL = F::PLANE;
   constexpr bool SPLIT = PassO<R, N>::SPLIT;
+  if (sT < 0) sT = 4L * fa.P;
   constexpr long NR = long(N) * N * N;
   __shared__ cx<R> sm[PassO<R, N>::NPL * PL];
   const PlaneWG<R, N> wg(fa);
@@ -1134,7 +1136,7 @@ __global__ void __launch_bounds__((Fz<R, N>::NTH)) k_fused_O(const cx<R>* buf4, 
   // the next partner's four pair planes are loaded into registers while this partner is transformed
   cx<R> pre[4][KP];
   auto fetch = [&](int q) {
-    const cx<R>* src = buf4 + (long(wg.t) * fa.P + q) * 4 * NR + wg.zo;
+    const cx<R>* src = buf4 + (long(wg.t) * sT + long(q) * sQ) * NR + wg.zo;
 #pragma unroll
     for (int f = 0; f < 4; ++f)
 #pragma unroll
@@ -1143,10 +1145,9 @@ __global__ void __launch_bounds__((Fz<R, N>::NTH)) k_fused_O(const cx<R>* buf4, 
   if (!SPLIT && wg.qb < wg.qe) fetch(wg.qb);
   for (int q = wg.qb; q < wg.qe; ++q) {
     const R wq = R(w[q]);
-    const long pair = long(wg.t) * fa.P + q;
     const double* del = dfr + 3 * pair_dindex(mi, ja, q, 0);
     const R k1 = R(double(mfreq<N>(wg.x)) + del[0]);
-    const cx<R>* src = buf4 + pair * 4 * NR + wg.zo;
+    const cx<R>* src = buf4 + (long(wg.t) * sT + long(q) * sQ) * NR + wg.zo;
 #pragma unroll 1
     for (int g = 0; g < (SPLIT ? 2 : 1); ++g) {
       const bool par = !SPLIT || g == 0, anti = !SPLIT || g == 1;

@@ -71,11 +71,11 @@ def test_every_term_fp64(case):
         assert err < FP64_TOL, (t, err)
 
 
-@pytest.mark.parametrize("batch", [0, 1, 3])
-def test_total_and_energy_fp64_with_batching(case, batch):
+@pytest.mark.parametrize("batch,store", [(0, True), (1, True), (3, True), (0, False), (3, False)])
+def test_total_and_energy_fp64_with_batching(case, batch, store):
     name, w, (per, tot, E) = case
-    _say(f"[gpu] {name} fp64 all terms batch={batch}")
-    op = tc.from_workload(w, precision=tc.TC_PREC_FP64, batch=batch)
+    _say(f"[gpu] {name} fp64 all terms batch={batch} pair_store={store}")
+    op = tc.from_workload(w, precision=tc.TC_PREC_FP64, batch=batch, pair_store=store)
     hc = op.apply()
     Eg, parts = op.energy()
     op.close()
