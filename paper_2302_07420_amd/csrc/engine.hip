@@ -1063,18 +1063,18 @@ struct EngineT : Engine {
 
   template <int OP>
   void zconv(hipStream_t s, const cx<R>* in, cx<R>* out, long npair, int t0, const MeshInfo& mi, const Tables& tb,
-             int sign) {
+             int sign, const cx<R>* inB = nullptr) {
     if constexpr (std::is_same<R, float>::value && N % 8 == 0) {
       if (zmfma) {
         const long groups = npair * (long(N) * N / 16);
         const unsigned nb = unsigned(std::min<long>((groups + 3) / 4, 8192));
         hipLaunchKernelGGL((k_zconv_mfma<N, OP>), dim3(nb), dim3(256), 0, s, in, out, npair, t0, mi, tb, sign,
-                           reinterpret_cast<const bf16x4*>(zfrag.p));
+                           reinterpret_cast<const bf16x4*>(zfrag.p), inB);
         return;
       }
     }
     hipLaunchKernelGGL((k_zconv<R, N, OP>), dim3(nblk(npair * N * N)), dim3(256), 0, s, in, out, npair, t0, mi, tb,
-                       sign);
+                       sign, inB);
   }
   template <int OP>
   void zconv(hipStream_t s, long npair, int t0, const MeshInfo& mi, const Tables& tb, int sign) {
@@ -1452,7 +1452,7 @@ struct EngineT : Engine {
           hipLaunchKernelGGL((k_band_dot<R, R, R>), dim3(nt * nbt * 3), dim3(256), 0, s, tP, NR, 0L, h4.p, 3 * NR, NR,
                              t0, (const cx<R>*)nullptr, 0L, t0, nbt, 3, NR, ts->OBh4);
         }
-        if (m.m3b6) {
+        if (m.m3b6 && !need_B) {
           K(TC_K_ZCONV_A2, fb * 5.0 * npair + tabB, [&] {
             zconv<OP_A2>(s, npair, t0, miT, tb, 1);
           });
@@ -1468,20 +1468,32 @@ struct EngineT : Engine {
       }
       TC_HIP(hipEventRecord(be[1], s));
       if (need_B) {
+        // With 3b6 selected, its z stage (Alg. 3b6, sources in bufA) and pass B's (Algs. 3b3-3b5, sources in
+        // bufB) share the parallel-channel u~ and one output: a single OP_A2 z stage takes the difference of
+        // the parallel inputs, and one partner sum serves both (three-body energy slot of pass B).
+        const bool merged = need_A && m.m3b6;
         const FusedArgs fy{P, nt, t0, S, chunk};
+        cx<R>* srcB = merged ? bufB.p : bufA.p;
+        cx<R>* zout = merged ? bufB.p + size_t(2) * npair * NR : bufB.p;
         K(TC_K_OTHER, fb * 13.0 * nt, [&] {
           hipLaunchKernelGGL((k_passB_Z<R, N>), dim3(nblk(long(nt) * NR)), dim3(256), 0, s, tP, tD, loc.p + NR,
                              h4.p, t0, nt, NTG, m, bm, Z.p);
         });
         K(TC_K_XY_PASSB, fb * (2.0 * npair + 4.0 * P + 4.0 * nt), [&] {
           hipLaunchKernelGGL((k_passB_xy<R, N>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, tP, X, Z.p,
-                             bitc ? H3bc.p : Hl.p, fy, miT, dfr.p, R(m.m3b5), bufA.p);
+                             bitc ? H3bc.p : Hl.p, fy, miT, dfr.p, R(m.m3b5), srcB);
         });
-        K(TC_K_ZCONV_B, fb * 3.0 * npair + tabB, [&] {
-          zconv<OP_B>(s, npair, t0, miT, tb, 1);
-        });
+        if (merged) {
+          K(TC_K_ZCONV_A2, fb * 7.0 * npair + tabB, [&] {
+            zconv<OP_A2>(s, bufA.p, zout, npair, t0, miT, tb, 1, bufB.p);
+          });
+        } else {
+          K(TC_K_ZCONV_B, fb * 3.0 * npair + tabB, [&] {
+            zconv<OP_B>(s, npair, t0, miT, tb, 1);
+          });
+        }
         K(TC_K_FUSED_Y, fb * (npair + P) + part, [&] {
-          hipLaunchKernelGGL((k_fused_Y<R, N>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, bufB.p, psi.p, sh.w.p,
+          hipLaunchKernelGGL((k_fused_Y<R, N>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, zout, psi.p, sh.w.p,
                              fy, 1.0, gpart.p);
         });
         K(TC_K_SUM_PARTS, part + 2.0 * fd * nt, [&] {
@@ -3117,7 +3129,7 @@ void finish_energy(tc_ctx* c) {
     const double* e = &ep[size_t(kAccSlots) * p];
     T += f * tk[p];
     // Two-body terms count 1/2, three-body terms 1/3 (multiplicities are in the operator).  Pass B (slot 3)
-    // fuses 2bx2 with 3b3-3b5; the 2bx2 bracket equals the 2bx1 bracket (slot 1, accumulated whenever
+    // fuses 2bx2 with 3b3-3b5 (and 3b6); the 2bx2 bracket equals the 2bx1 bracket (slot 1, accumulated whenever
     // either is selected) because the discrete kernels are transposes of each other, so it is moved from
     // the 1/3 to the 1/2 group through slot 1.
     E2 += f * 0.5 * (e[0] + e[4] + e[5] + (m.m2bx1 + m.m2bx2) * e[1]);

@@ -604,6 +604,8 @@ k_passB_xy(const cx<R>* psi, const cx<R>* chi, const cx<R>* Zl, const cx<R>* Hl,
 //          W0_s = u~_s rho, W3_s = i kappa_3 u~_s rho
 //   OP_A2: 4 -> 1  -i sum_s u~_s (P_s + kappa_3 R_s), inputs [P_par, R_par, P_anti, R_anti]
 //   OP_B : 2 -> 1  +i u~_par (P + kappa_3 R), inputs [P, R]
+// OP_A2 with inB ([pair][2] pass-B sources [P_B, R_B]): -u~_par (P_B + kappa_3 R_B) joins the sum, so that
+// the one output is the sum of the OP_A2 and OP_B outputs (both take u~_par).
 template <int OP>
 struct OpShape;
 template <> struct OpShape<OP_A1> { static constexpr int nin = 1, nout = 5; };
@@ -611,9 +613,14 @@ template <> struct OpShape<OP_O> { static constexpr int nin = 1, nout = 4; };
 template <> struct OpShape<OP_A2> { static constexpr int nin = 4, nout = 1; };
 template <> struct OpShape<OP_B> { static constexpr int nin = 2, nout = 1; };
 
+// occupancy target: 3 waves per SIMD for FP32 at 24^3 (every operation fits 168 registers there)
+template <typename R, int N>
+constexpr int kZconvWaves = (sizeof(R) == 4 && N == 24) ? 3 : 1;
+
 template <typename R, int N, int OP>
-__global__ void __launch_bounds__(256) k_zconv(const cx<R>* in, cx<R>* out, long npairs, int t0, MeshInfo mi,
-                                               Tables tb, int sign_target_minus_partner) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kZconvWaves<R, N>))) k_zconv(const cx<R>* in, cx<R>* out, long npairs, int t0, MeshInfo mi,
+                                               Tables tb, int sign_target_minus_partner,
+                                               const cx<R>* inB = nullptr) {
   constexpr int NN = N * N;
   constexpr long NR = long(N) * N * N;
   constexpr int NIN = OpShape<OP>::nin, NOUT = OpShape<OP>::nout;
@@ -664,19 +671,24 @@ __global__ void __launch_bounds__(256) k_zconv(const cx<R>* in, cx<R>* out, long
     cx<R> acc[N], v[N];
 #pragma unroll
     for (int z = 0; z < N; ++z) acc[z] = mk<R>(R(0), R(0));
+    // channels: the NIN / 2 input pairs, then (OP_A2 with inB) the pass-B sources with u~_par and sign -1
+    const int nch = NIN / 2 + ((OP == OP_A2 && inB) ? 1 : 0);
 #pragma unroll 1
-    for (int s = 0; s < NIN / 2; ++s) {
-      const cx<R>* b = in + (pair * NIN + 2 * s) * NR + xy;
+    for (int s = 0; s < nch; ++s) {
+      const bool isB = s == NIN / 2;
+      const cx<R>* b = isB ? inB + pair * 2 * NR + xy : in + (pair * NIN + 2 * s) * NR + xy;
+      const R* tu = (s == 1 && !isB) ? tU[1] : tU[0];
+      const R sg = isB ? R(-1) : R(1);
 #pragma unroll
       for (int z = 0; z < N; ++z) v[z] = b[z * NN];
       fft_line<R, N, -1>(v);
 #pragma unroll
-      for (int z = 0; z < N; ++z) acc[z] = acc[z] + tU[s][z * NN] * v[z];
+      for (int z = 0; z < N; ++z) acc[z] = acc[z] + (sg * tu[z * NN]) * v[z];
 #pragma unroll
       for (int z = 0; z < N; ++z) v[z] = b[NR + z * NN];
       fft_line<R, N, -1>(v);
 #pragma unroll
-      for (int z = 0; z < N; ++z) acc[z] = acc[z] + ((R(mfreq<N>(z)) + d3) * tU[s][z * NN]) * v[z];
+      for (int z = 0; z < N; ++z) acc[z] = acc[z] + ((R(mfreq<N>(z)) + d3) * (sg * tu[z * NN])) * v[z];
     }
 #pragma unroll
     for (int z = 0; z < N; ++z) acc[z] = OP == OP_A2 ? mul_i(R(-1) * acc[z]) : mul_i(acc[z]);
@@ -774,7 +786,7 @@ __device__ __forceinline__ f32x4 imul_scale(const f32x4& v, float a, float b) { 
 template <int N, int OP>
 __global__ void __launch_bounds__(256) k_zconv_mfma(const cx<float>* in, cx<float>* out, long npairs, int t0,
                                                     MeshInfo mi, Tables tb, int sign_target_minus_partner,
-                                                    const bf16x4* frag_g) {
+                                                    const bf16x4* frag_g, const cx<float>* inB = nullptr) {
   using Z = ZMfma<N>;
   constexpr int NT = Z::NT, NN = N * N, GPP = NN / 16;   // column groups per pair
   constexpr long NR = long(N) * N * N;
@@ -817,6 +829,17 @@ __global__ void __launch_bounds__(256) k_zconv_mfma(const cx<float>* in, cx<floa
     col_base(grp, pair, xy);
 #pragma unroll
     for (int c = 0; c < NIN; ++c) load_col(in + (pair * NIN + c) * NR + xy, pre[c]);
+    if constexpr (OP == OP_A2) {
+      if (inB) {   // parallel inputs minus the pass-B sources
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+          f32x4 b[NT];
+          load_col(inB + (pair * 2 + c) * NR + xy, b);
+#pragma unroll
+          for (int m = 0; m < NT; ++m) pre[c][m] -= b[m];
+        }
+      }
+    }
   };
   long grp = long(blockIdx.x) * 4 + wave;
   if (kPrefetch && grp < ngroups) fetch(grp);
@@ -1460,7 +1483,8 @@ __global__ void k_sum_parts(int mode, int S, int T, int t0, int slot, const R* h
 // Local (Hartree-type) terms added to the FP64 accumulators, then g_t = sum of the slots that belong to
 // the operator.  loc: [VH, h1 x3, P2bh2, F3b1, h6, F3b2]; D is stored component-major D[(c*P + p)*N^3 + r].
 // acc slots (kAccSlots): 0 = 2ah + 2ax, 1 = 2bx1 (unit weight; enters g times the 2bx1 multiplier), 2 = three-body
-// terms outside pass B, 3 = pass B (2bx2, 3b3, 3b4, 3b5), 4 = 2bh1, 5 = 2bh2.
+// terms outside pass B, 3 = pass B (2bx2, 3b3, 3b4, 3b5, and 3b6 when selected with any of them), 4 = 2bh1,
+// 5 = 2bh2.
 constexpr int kAccSlots = 6;
 
 template <typename R, int N>
