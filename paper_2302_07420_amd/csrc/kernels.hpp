@@ -937,9 +937,14 @@ struct PassA {
   static constexpr int NPL = SPLIT ? 4 : 7;
 };
 
+// occupancy target: 3 waves per SIMD where that costs no spills (FP32 at 24^3)
+template <typename R, int N>
+constexpr int kFusedAWaves = (sizeof(R) == 4 && N == 24) ? 3 : 1;
+
 // POL (spin-polarised runs): the antiparallel-channel 3b6 sources take the other spin's density nA.
 template <typename R, int N, bool POL = false>
-__global__ void __launch_bounds__((Fz<R, N>::NTH)) k_fused_A(const cx<R>* buf5, const cx<R>* psi, const cx<R>* Dl,
+__global__ void __launch_bounds__((Fz<R, N>::NTH)) __attribute__((amdgpu_waves_per_eu(kFusedAWaves<R, N>)))
+k_fused_A(const cx<R>* buf5, const cx<R>* psi, const cx<R>* Dl,
                                                            const cx<R>* Hl, const cx<R>* n, const double* w,
                                                            FusedArgs fa, Masks m, int do3b6, MeshInfo mi,
                                                            Basis<R> B, Basis<R> M, const double* dfr, cx<R>* src4,
@@ -1048,6 +1053,13 @@ __global__ void __launch_bounds__((Fz<R, N>::NTH)) k_fused_A(const cx<R>* buf5, 
           for (int d = 0; d < 3; ++d) sm[(ab + d) * PL + so] = T[d] * nanti;
         }
       }
+      // finish this partner's multiply-accumulates here (a compiler-only fence: no instruction), so that
+      // the partner fields loaded for them are not kept live across the forward transforms
+#pragma unroll
+      for (int i = 0; i < KP; ++i)
+#pragma unroll
+        for (int s = 0; s < 3; ++s)
+          asm volatile("" : "+v"(ga[i][s].x), "+v"(ga[i][s].y), "+v"(h4[i][s].x), "+v"(h4[i][s].y));
       __syncthreads();
       if (do3b6) {
         // forward xy of the T planes (slots 1..6 unsplit; 1..3 or 0..2 split), then the split form
