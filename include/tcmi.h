@@ -329,7 +329,9 @@ int tc_sync(tc_ctx* ctx);
 /* Milliseconds of device time of the last tc_apply_all*, measured with events on
  * the context's stream; kernel_ms[0..n) receives the per-stage breakdown
  * (stages: 0 G->r, 1 densities and Hartree fields, 2 occupied-occupied pass,
- * 3 pass A, 4 pass B, 5 r->G and FP64 corrections). */
+ * 3 pass A, 4 pass B, 5 r->G and FP64 corrections).  With the resident pair store
+ * (tc_set_pair_store) stage 2 includes pass A's pair densities and first z stage, and
+ * with 3b6 and pass-B terms both selected stage 4 includes the shared last z stage. */
 int tc_last_timing(tc_ctx* ctx, double* total_ms, double* stage_ms, int n);
 
 /* Number of target orbitals processed per pass-A/B batch (and occupied partners per
