@@ -408,7 +408,9 @@ struct Fz {
 };
 
 // in-place 2D transform of np planes in LDS ([np][N][N+1]); thread row p takes planes p, p + RB, ...;
-// ends with a barrier
+// ends with a barrier.  The plane kernels below write and read LDS outside these transforms only at the
+// points each thread owns (so0 + RB LD i), so a round's reads after a transform and the next round's
+// writes need no barrier between them: only the barrier before the next transform.
 template <typename R, int N, int DIR>
 __device__ __forceinline__ void planes_fft(cx<R>* sm, int np, int tid) {
   constexpr int LD = N + 1, RB = Fz<R, N>::RB;
@@ -508,7 +510,6 @@ __global__ void __launch_bounds__((Fz<R, N>::NTH)) k_pair_xy(const cx<R>* bra, c
 #pragma unroll
       for (int i = 0; i < KP; ++i) dst[RB * N * i] = sm[cc * F::PLANE + wg.so0 + RB * F::LD * i];
     }
-    __syncthreads();
   }
 }
 
@@ -593,7 +594,6 @@ k_passB_xy(const cx<R>* psi, const cx<R>* chi, const cx<R>* Zl, const cx<R>* Hl,
         dst[NR + r] = sm[so + 2 * F::PLANE];
       }
     }
-    __syncthreads();
   }
 }
 
@@ -1080,7 +1080,6 @@ k_fused_A(const cx<R>* buf5, const cx<R>* psi, const cx<R>* Dl,
             sto(dst + 3 * NR, ob[i], sm[(ab + 2) * PL + so]);
           }
         }
-        __syncthreads();
       }
     }
   }
@@ -1127,7 +1126,6 @@ __global__ void __launch_bounds__((Fz<R, N>::NTH)) k_fused_Y(const cx<R>* buf1, 
       for (int cc = 0; cc < nq; ++cc)
         cfma(ga[i], R(coef * w[q0 + cc]), sm[cc * F::PLANE + so], psi[long(q0 + cc) * NR + r]);
     }
-    __syncthreads();
   }
 #pragma unroll
   for (int i = 0; i < KP; ++i) gpart[(long(wg.c) * fa.T + wg.t) * NR + wg.zo + RB * N * i] = ga[i];
@@ -1240,7 +1238,6 @@ __global__ void __launch_bounds__((Fz<R, N>::NTH)) k_fused_O(const cx<R>* buf4, 
           }
         }
       }
-      __syncthreads();
     }
   }
 #pragma unroll
