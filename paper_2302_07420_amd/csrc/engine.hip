@@ -1103,6 +1103,19 @@ struct EngineT : Engine {
     return true;
   }
 
+  // Bytes of per-batch pair buffers: an eighth of the device's memory, between 8 and 32 GiB (32 GiB on a
+  // 288 GB device: 128 targets per batch at 256 orbitals and 24^3 in FP32).  Larger batches mean fewer,
+  // larger launches and fewer partial tails.
+  size_t budget_ = 0;
+  size_t pair_budget() {
+    if (!budget_) {
+      size_t fr = 0, tot = 0;
+      if (hipMemGetInfo(&fr, &tot) != hipSuccess) tot = 0;
+      budget_ = std::min(size_t(32) << 30, std::max(size_t(8) << 30, tot / 8));
+    }
+    return budget_;
+  }
+
   void ensure(const Problem& pb, size_t budget_bytes) {
     const int P = pb.P();
     if (P == P_alloc && pb.batch == batch_alloc && pb.bitc == bitc_alloc && pb.nspin == nspin_alloc) return;
@@ -1182,7 +1195,7 @@ struct EngineT : Engine {
       m.m2bx1 = -m.m2bx1;
       m.m2bx2 = -m.m2bx2;
     }
-    ensure(pb, size_t(8) << 30);
+    ensure(pb, pair_budget());
     // targets: the orbitals, or nbt trial vectors per k-point
     const int nbt = ts ? ts->nvec : nb;
     const int NTG = (ts && ts->nblk ? ts->nblk : pb.nk) * nbt;
@@ -1625,7 +1638,7 @@ struct EngineT : Engine {
     const int nirr = int(pb.irr.size());
     const int PI = nirr * nb;
     const Masks m = make_masks(pb.mask);
-    ensure(pb, size_t(8) << 30);
+    ensure(pb, pair_budget());
     const MeshInfo mi{pb.n1, pb.n2, pb.n3, nb, P, nb, sh.irrk.p};   // rows / targets: representatives
     Recip rc;
     for (int i = 0; i < 9; ++i) rc.b[i] = pb.B[i];
@@ -1868,7 +1881,7 @@ struct EngineT : Engine {
     const int nb = pb.nb;
     const int npm = pb.npw_max;
     const Masks m = make_masks(pb.mask);
-    ensure(pb, size_t(8) << 30);
+    ensure(pb, pair_budget());
     const MeshInfo mi{pb.n1, pb.n2, pb.n3, nb, P, nb};
     Recip rc;
     for (int i = 0; i < 9; ++i) rc.b[i] = pb.B[i];
