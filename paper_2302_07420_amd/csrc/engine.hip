@@ -841,7 +841,7 @@ struct EngineT : Engine {
   DBuf<cx<R>> H3a4;    // [P][3][NR]
   DBuf<R> h5;          // [P][NR]
   DBuf<cx<R>> bufA;    // [T*P][4][NR]  pair densities, 3b6 and pass-B sources
-  DBuf<cx<R>> bufB;    // [T*P][5][NR]  z-stage outputs
+  DBuf<cx<R>> bufB;    // [T*P][5][NR]  z-stage outputs; after pass A, pass-B sources and the shared z-stage output
   DBuf<cx<R>> allB;    // [P*P][5][NR]  pass-A z-stage outputs of every pair (resident store)
   DBuf<cx<R>> h4, Z;   // [T][3][NR]  h4 (Cartesian), pass-B target factor (lattice)
   DBuf<cx<R>> g;       // [T][NR]
@@ -1104,7 +1104,7 @@ struct EngineT : Engine {
   }
 
   // Bytes of per-batch pair buffers: an eighth of the device's memory, between 8 and 32 GiB (32 GiB on a
-  // 288 GB device: 128 targets per batch at 256 orbitals and 24^3 in FP32).  Larger batches mean fewer,
+  // 288 GB device: 134 targets per batch at 256 orbitals and 24^3 in FP32).  Larger batches mean fewer,
   // larger launches and fewer partial tails.
   size_t budget_ = 0;
   size_t pair_budget() {
@@ -1482,8 +1482,9 @@ struct EngineT : Engine {
       TC_HIP(hipEventRecord(be[1], s));
       if (need_B) {
         // With 3b6 selected, its z stage (Alg. 3b6, sources in bufA) and pass B's (Algs. 3b3-3b5, sources in
-        // bufB) share the parallel-channel u~ and one output: a single OP_A2 z stage takes the difference of
-        // the parallel inputs, and one partner sum serves both (three-body energy slot of pass B).
+        // bufB) both multiply by the parallel-channel u~ and end in the same partner sum: one OP_A2 z stage
+        // also takes the pass-B sources (with -u~_par: OP_A2 carries -i where pass B carries +i), and one
+        // partner sum serves both (three-body energy slot of pass B).
         const bool merged = need_A && m.m3b6;
         const FusedArgs fy{P, nt, t0, S, chunk};
         cx<R>* srcB = merged ? bufB.p : bufA.p;
