@@ -1157,9 +1157,23 @@ __global__ void __launch_bounds__((Fz<R, N>::NTH)) k_fused_O(const cx<R>* buf4, 
   __shared__ cx<R> sm[PassO<R, N>::NPL * PL];
   const PlaneWG<R, N> wg(fa);
   const Basis<R> B = basis<R>(rc);
+  // |X|^2 of a Cartesian vector X_c = sum_d B_dc Y_d from its lattice components: Y^H M Y with the metric
+  // M = B B^T (diagonal Md, twice the off-diagonal Mo for the pairs 12, 13, 23)
+  R Md[3], Mo[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d)
+    Md[d] = B.b[3 * d] * B.b[3 * d] + B.b[3 * d + 1] * B.b[3 * d + 1] + B.b[3 * d + 2] * B.b[3 * d + 2];
+  Mo[0] = R(2) * (B.b[0] * B.b[3] + B.b[1] * B.b[4] + B.b[2] * B.b[5]);
+  Mo[1] = R(2) * (B.b[0] * B.b[6] + B.b[1] * B.b[7] + B.b[2] * B.b[8]);
+  Mo[2] = R(2) * (B.b[3] * B.b[6] + B.b[4] * B.b[7] + B.b[5] * B.b[8]);
+  auto norm2 = [&](const cx<R>* Y) {
+    return Md[0] * (Y[0].x * Y[0].x + Y[0].y * Y[0].y) + Md[1] * (Y[1].x * Y[1].x + Y[1].y * Y[1].y) +
+           Md[2] * (Y[2].x * Y[2].x + Y[2].y * Y[2].y) + Mo[0] * (Y[0].x * Y[1].x + Y[0].y * Y[1].y) +
+           Mo[1] * (Y[0].x * Y[2].x + Y[0].y * Y[2].y) + Mo[2] * (Y[1].x * Y[2].x + Y[1].y * Y[2].y);
+  };
   const int ja = fa.t0 + wg.t;
   R h5[KP], h5b[SPLITH ? KP : 1];
-  cx<R> H[KP][3];
+  cx<R> H[KP][3];   // lattice components (conj(X_c) = sum_d B_dc conj(Y_d)), made Cartesian at the end
 #pragma unroll
   for (int i = 0; i < KP; ++i) {
     h5[i] = R(0);
@@ -1210,32 +1224,27 @@ __global__ void __launch_bounds__((Fz<R, N>::NTH)) k_fused_O(const cx<R>* buf4, 
       for (int i = 0; i < KP; ++i) {
         const long r = wg.zo + RB * N * i;
         const int so = wg.so0 + RB * F::LD * i;
-        cx<R> Y[3], X[3];
+        cx<R> Y[3];
         if (par) {
           const cx<R> pq = psi[long(q) * NR + r];
 #pragma unroll
           for (int d = 0; d < 3; ++d) Y[d] = sm[d * PL + so];
-          to_cart(B, Y, X);
+          h5[i] += wq * norm2(Y);
 #pragma unroll
-          for (int cd = 0; cd < 3; ++cd) {
-            h5[i] += wq * (X[cd].x * X[cd].x + X[cd].y * X[cd].y);
-            const cx<R> hv = cmulc(X[cd], pq);
-            H[i][cd].x += wq * hv.x;
-            H[i][cd].y += wq * hv.y;
+          for (int d = 0; d < 3; ++d) {
+            const cx<R> hv = cmulc(Y[d], pq);
+            H[i][d].x += wq * hv.x;
+            H[i][d].y += wq * hv.y;
           }
         }
         if (anti) {
 #pragma unroll
           for (int d = 0; d < 3; ++d) Y[d] = sm[(ab + d) * PL + so];
-          to_cart(B, Y, X);
-#pragma unroll
-          for (int cd = 0; cd < 3; ++cd) {
-            const R v = wq * (X[cd].x * X[cd].x + X[cd].y * X[cd].y);
-            if constexpr (SPLITH)
-              h5b[i] += v;
-            else
-              h5[i] += v;
-          }
+          const R v = wq * norm2(Y);
+          if constexpr (SPLITH)
+            h5b[i] += v;
+          else
+            h5[i] += v;
         }
       }
     }
@@ -1245,8 +1254,10 @@ __global__ void __launch_bounds__((Fz<R, N>::NTH)) k_fused_O(const cx<R>* buf4, 
     const long r = wg.zo + RB * N * i;
     h5part[(long(wg.c) * fa.T + wg.t) * NR + r] = h5[i];
     if constexpr (SPLITH) h5part[(long(fa.S + wg.c) * fa.T + wg.t) * NR + r] = h5b[i];
+    cx<R> Hc[3];
+    to_cart(B, H[i], Hc);
 #pragma unroll
-    for (int cd = 0; cd < 3; ++cd) H3part[((long(wg.c) * fa.T + wg.t) * 3 + cd) * NR + r] = H[i][cd];
+    for (int cd = 0; cd < 3; ++cd) H3part[((long(wg.c) * fa.T + wg.t) * 3 + cd) * NR + r] = Hc[cd];
   }
 }
 
