@@ -169,3 +169,21 @@ def test_orbital_energies(case, prec, tol):
     _say(f"    max |eps - eps_oracle| / max |eps| = {err:.3e}")
     assert err < tol
     np.testing.assert_array_equal(got, g2)
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-13), ("fp32", 2e-6)])
+def test_shared_last_z_stage_equals_separate_stages(case, prec, tol):
+    """3b6 selected with pass-B terms runs one shared z stage and one partner sum; selected apart, each
+    keeps its own.  The operator is linear in the selected terms, so the two must agree."""
+    name, w, _ = case
+    _say(f"[gpu] {name} {prec} shared 3b6 / pass-B z stage vs separate")
+    P = tc.TC_PREC_FP64 if prec == "fp64" else tc.TC_PREC_FP32
+    b3b6 = tc.TERM_BITS["3b6"]
+    bB = tc.TERM_BITS["2bx2"] | tc.TERM_BITS["3b3"] | tc.TERM_BITS["3b4"] | tc.TERM_BITS["3b5"]
+    out = {}
+    for key, mask in (("both", b3b6 | bB), ("3b6", b3b6), ("B", bB)):
+        op = tc.from_workload(w, precision=P, terms=mask, div_correction=False)
+        out[key] = op.apply()
+        op.close()
+    sep = [a + b for a, b in zip(out["3b6"], out["B"])]
+    assert relerr(out["both"], sep) < tol
