@@ -793,6 +793,7 @@ struct Engine {
   virtual void apply(hipStream_t s, Shared& sh, const Problem& pb, double* stage_ms,
                      const TargetSet* ts = nullptr) = 0;
   virtual void apply_sym(hipStream_t s, Shared& sh, const Problem& pb, double* stage_ms) = 0;
+  virtual void release_pair_store() = 0;
   Prof* prof = nullptr;
 };
 
@@ -1080,6 +1081,8 @@ struct EngineT : Engine {
   void zconv(hipStream_t s, long npair, int t0, const MeshInfo& mi, const Tables& tb, int sign) {
     zconv<OP>(s, bufA.p, bufB.p, npair, t0, mi, tb, sign);
   }
+
+  void release_pair_store() override { allB.release(); }
 
   // The resident store of pass-A z-stage outputs: allocated when it leaves a quarter of the device (at
   // least 16 GiB) free, released when it does not fit.
@@ -4016,6 +4019,10 @@ int tc_set_batch(tc_ctx* c, int targets_per_batch) {
 int tc_set_pair_store(tc_ctx* c, int on) {
   return guard(c, [&]() -> int {
     c->pb.pair_store = on != 0;
+    if (!on && c->eng) {   // release now (the stream's queued work may still read it)
+      TC_HIP(hipStreamSynchronize(c->stream));
+      c->eng->release_pair_store();
+    }
     c->have_result = false;
     return TC_OK;
   });

@@ -187,3 +187,19 @@ def test_shared_last_z_stage_equals_separate_stages(case, prec, tol):
         op.close()
     sep = [a + b for a, b in zip(out["3b6"], out["B"])]
     assert relerr(out["both"], sep) < tol
+
+
+def test_pair_store_switch_on_a_live_context(case):
+    """The resident store can be switched off (released at once) and on again between applications."""
+    name, w, (per, tot, E) = case
+    _say(f"[gpu] {name} fp64 pair store on -> off -> on")
+    op = tc.from_workload(w, precision=tc.TC_PREC_FP64)
+    runs = [op.apply()]
+    op.set_pair_store(False)
+    runs.append(op.apply())
+    op.set_pair_store(True)
+    runs.append(op.apply())
+    op.close()
+    for hc in runs:
+        assert relerr(hc, tot) < FP64_TOL
+    assert relerr(runs[1], runs[0]) < 1e-13 and relerr(runs[2], runs[0]) < 1e-15
