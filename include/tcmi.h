@@ -103,7 +103,7 @@ int tc_set_cell(tc_ctx* ctx, const double lattice[9]);
  * uniform SCF mesh).  Each n_i in [1, 16]. */
 int tc_set_kmesh(tc_ctx* ctx, int n1, int n2, int n3);
 
-/* FFT grid.  This build supports cubic grids N1 = N2 = N3 = N with
+/* FFT grid.  The library supports cubic grids N1 = N2 = N3 = N with
  * N in {8, 12, 16, 24, 32, 48}; anything else is TC_ERR_UNSUPPORTED. */
 int tc_set_grid(tc_ctx* ctx, int N1, int N2, int N3);
 

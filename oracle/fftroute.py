@@ -19,7 +19,7 @@ Conventions (restating the paper's Secs. 2.2, 2.3 and 2.6 in the units used here
   * g_j(r) is the cell-periodic part of a term applied to phi_j, with the
     weights f_q / N_k of the algorithms.
 
-Readings where the paper is silent or garbled (each restated in the design doc):
+Readings where the paper is silent or garbled:
   R1  Q = Delta+G = 0: in Hartree-type fields every kernel is dropped (Alg. 2ah
       text); in exchange-type convolutions 1/r is dropped (replaced by the GB
       correction), the Jastrow-derived scalar kernels take their finite limits
