@@ -1796,7 +1796,7 @@ struct EngineT : Engine {
           hipLaunchKernelGGL((k_sum_parts<R, N>), dim3(nblk(long(nt) * NR)), dim3(256), 0, s, 1, S, nt, t0, 0, nullptr,
                              nullptr, gpart.p, h4part.p, nullptr, nullptr, acc.p, h4.p);
         });
-        if (m.m3b6) {
+        if (m.m3b6 && !need_B) {   // else shared with pass B below
           K(TC_K_ZCONV_A2, fb * 5.0 * npair + tabB, [&] {
             zconv<OP_A2>(s, npair, t0, mi, tb, 1);
           });
@@ -1812,20 +1812,30 @@ struct EngineT : Engine {
       }
       TC_HIP(hipEventRecord(bev.e[1], s));
       if (need_B) {
+        // 3b6 and pass B share one z stage and one partner sum (as in the unreduced path)
+        const bool merged = need_A && m.m3b6;
         const FusedArgs fy{P, nt, t0, S, chunk};
+        cx<R>* srcB = merged ? bufB.p : bufA.p;
+        cx<R>* zout = merged ? bufB.p + size_t(2) * npair * NR : bufB.p;
         K(TC_K_OTHER, fb * 13.0 * nt, [&] {
           hipLaunchKernelGGL((k_passB_Z<R, N>), dim3(nblk(long(nt) * NR)), dim3(256), 0, s, psiT.p, DT.p, loc.p + NR,
                              h4.p, t0, nt, PI, m, bm, Z.p);
         });
         K(TC_K_XY_PASSB, fb * (2.0 * npair + 4.0 * P + 4.0 * nt), [&] {
           hipLaunchKernelGGL((k_passB_xy<R, N>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, psiT.p, psi.p, Z.p, Hl.p,
-                             fy, mi, dfr.p, R(m.m3b5), bufA.p);
+                             fy, mi, dfr.p, R(m.m3b5), srcB);
         });
-        K(TC_K_ZCONV_B, fb * 3.0 * npair + tabB, [&] {
-          zconv<OP_B>(s, npair, t0, mi, tb, 1);
-        });
+        if (merged) {
+          K(TC_K_ZCONV_A2, fb * 7.0 * npair + tabB, [&] {
+            zconv<OP_A2>(s, bufA.p, zout, npair, t0, mi, tb, 1, bufB.p);
+          });
+        } else {
+          K(TC_K_ZCONV_B, fb * 3.0 * npair + tabB, [&] {
+            zconv<OP_B>(s, npair, t0, mi, tb, 1);
+          });
+        }
         K(TC_K_FUSED_Y, fb * (npair + P) + part, [&] {
-          hipLaunchKernelGGL((k_fused_Y<R, N>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, bufB.p, psi.p, sh.w.p,
+          hipLaunchKernelGGL((k_fused_Y<R, N>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, zout, psi.p, sh.w.p,
                              fy, 1.0, gpart.p);
         });
         K(TC_K_SUM_PARTS, part + 2.0 * fd * nt, [&] {
@@ -2068,7 +2078,7 @@ struct EngineT : Engine {
             hipLaunchKernelGGL((k_sum_parts<R, N>), dim3(nblk(long(nt) * NR)), dim3(256), 0, s, 1, S, nt, t0, 0,
                                nullptr, nullptr, gpart.p, h4part.p, nullptr, nullptr, acc.p, h4.p);
           });
-          if (m.m3b6) {
+          if (m.m3b6 && !need_B) {   // else shared with pass B below
             K(TC_K_ZCONV_A2, fb * 5.0 * npair + tabB, [&] {
               zconv<OP_A2>(s, npair, t0, mi, tb, 1);
             });
@@ -2084,20 +2094,30 @@ struct EngineT : Engine {
         }
         TC_HIP(hipEventRecord(bev.e[1], s));
         if (need_B) {
+          // 3b6 and pass B share one z stage and one partner sum (as in the unpolarised path)
+          const bool merged = need_A && m.m3b6;
           const FusedArgs fy{P, nt, t0, S, chunk};
+          cx<R>* srcB = merged ? bufB.p : bufA.p;
+          cx<R>* zout = merged ? bufB.p + size_t(2) * npair * NR : bufB.p;
           K(TC_K_OTHER, fb * 13.0 * nt, [&] {
             hipLaunchKernelGGL((k_passB_Z<R, N>), dim3(nblk(long(nt) * NR)), dim3(256), 0, s, PSI[sp], DD[sp],
                                LOC[sp] + NR, h4.p, t0, nt, P, m, bm, Z.p);
           });
           K(TC_K_XY_PASSB, fb * (2.0 * npair + 4.0 * P + 4.0 * nt), [&] {
             hipLaunchKernelGGL((k_passB_xy<R, N>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, PSI[sp], PSI[sp], Z.p,
-                               HL[sp], fy, mi, dfr.p, R(m.m3b5), bufA.p);
+                               HL[sp], fy, mi, dfr.p, R(m.m3b5), srcB);
           });
-          K(TC_K_ZCONV_B, fb * 3.0 * npair + tabB, [&] {
-            zconv<OP_B>(s, npair, t0, mi, tb, 1);
-          });
+          if (merged) {
+            K(TC_K_ZCONV_A2, fb * 7.0 * npair + tabB, [&] {
+              zconv<OP_A2>(s, bufA.p, zout, npair, t0, mi, tb, 1, bufB.p);
+            });
+          } else {
+            K(TC_K_ZCONV_B, fb * 3.0 * npair + tabB, [&] {
+              zconv<OP_B>(s, npair, t0, mi, tb, 1);
+            });
+          }
           K(TC_K_FUSED_Y, fb * (npair + P) + part, [&] {
-            hipLaunchKernelGGL((k_fused_Y<R, N>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, bufB.p, PSI[sp], W[sp],
+            hipLaunchKernelGGL((k_fused_Y<R, N>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, zout, PSI[sp], W[sp],
                                fy, 1.0, gpart.p);
           });
           K(TC_K_SUM_PARTS, part + 2.0 * fd * nt, [&] {
