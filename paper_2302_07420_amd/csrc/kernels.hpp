@@ -783,8 +783,12 @@ __device__ __forceinline__ f32x4 imul_scale(const f32x4& v, float a, float b) { 
   return f32x4{-a * v.y, a * v.x, -b * v.w, b * v.z};
 }
 
+// occupancy target at 24 points: 2 waves per SIMD for the many-to-one stages, 3 for the others
 template <int N, int OP>
-__global__ void __launch_bounds__(256) k_zconv_mfma(const cx<float>* in, cx<float>* out, long npairs, int t0,
+constexpr int kZMfmaWaves = N == 24 ? ((OP == OP_A2 || OP == OP_B) ? 2 : 3) : 1;
+
+template <int N, int OP>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kZMfmaWaves<N, OP>))) k_zconv_mfma(const cx<float>* in, cx<float>* out, long npairs, int t0,
                                                     MeshInfo mi, Tables tb, int sign_target_minus_partner,
                                                     const bf16x4* frag_g, const cx<float>* inB = nullptr) {
   using Z = ZMfma<N>;
