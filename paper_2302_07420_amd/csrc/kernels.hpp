@@ -618,9 +618,9 @@ template <typename R, int N>
 constexpr int kZconvWaves = (sizeof(R) == 4 && N == 24) ? 3 : 1;
 
 template <typename R, int N, int OP>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kZconvWaves<R, N>))) k_zconv(const cx<R>* in, cx<R>* out, long npairs, int t0, MeshInfo mi,
-                                               Tables tb, int sign_target_minus_partner,
-                                               const cx<R>* inB = nullptr) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kZconvWaves<R, N>)))
+k_zconv(const cx<R>* in, cx<R>* out, long npairs, int t0, MeshInfo mi, Tables tb, int sign_target_minus_partner,
+        const cx<R>* inB = nullptr) {
   constexpr int NN = N * N;
   constexpr long NR = long(N) * N * N;
   constexpr int NIN = OpShape<OP>::nin, NOUT = OpShape<OP>::nout;
@@ -788,9 +788,9 @@ template <int N, int OP>
 constexpr int kZMfmaWaves = N == 24 ? ((OP == OP_A2 || OP == OP_B) ? 2 : 3) : 1;
 
 template <int N, int OP>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kZMfmaWaves<N, OP>))) k_zconv_mfma(const cx<float>* in, cx<float>* out, long npairs, int t0,
-                                                    MeshInfo mi, Tables tb, int sign_target_minus_partner,
-                                                    const bf16x4* frag_g, const cx<float>* inB = nullptr) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kZMfmaWaves<N, OP>)))
+k_zconv_mfma(const cx<float>* in, cx<float>* out, long npairs, int t0, MeshInfo mi, Tables tb,
+             int sign_target_minus_partner, const bf16x4* frag_g, const cx<float>* inB = nullptr) {
   using Z = ZMfma<N>;
   constexpr int NT = Z::NT, NN = N * N, GPP = NN / 16;   // column groups per pair
   constexpr long NR = long(N) * N * N;
@@ -948,11 +948,9 @@ constexpr int kFusedAWaves = (sizeof(R) == 4 && N == 24) ? 3 : 1;
 // POL (spin-polarised runs): the antiparallel-channel 3b6 sources take the other spin's density nA.
 template <typename R, int N, bool POL = false>
 __global__ void __launch_bounds__((Fz<R, N>::NTH)) __attribute__((amdgpu_waves_per_eu(kFusedAWaves<R, N>)))
-k_fused_A(const cx<R>* buf5, const cx<R>* psi, const cx<R>* Dl,
-                                                           const cx<R>* Hl, const cx<R>* n, const double* w,
-                                                           FusedArgs fa, Masks m, int do3b6, MeshInfo mi,
-                                                           Basis<R> B, Basis<R> M, const double* dfr, cx<R>* src4,
-                                                           cx<R>* gpart, cx<R>* h4part, const cx<R>* nA = nullptr) {
+k_fused_A(const cx<R>* buf5, const cx<R>* psi, const cx<R>* Dl, const cx<R>* Hl, const cx<R>* n, const double* w,
+          FusedArgs fa, Masks m, int do3b6, MeshInfo mi, Basis<R> B, Basis<R> M, const double* dfr, cx<R>* src4,
+          cx<R>* gpart, cx<R>* h4part, const cx<R>* nA = nullptr) {
   using F = Fz<R, N>;
   constexpr int KP = F::KP, RB = F::RB, PL = F::PLANE;
   constexpr bool SPLIT = PassA<R, N>::SPLIT;
