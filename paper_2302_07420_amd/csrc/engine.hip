@@ -1454,9 +1454,14 @@ struct EngineT : Engine {
           });
         }
         K(TC_K_FUSED_A, fb * ((m.m3b6 ? 9.0 : 5.0) * npair + 8.0 * P + nt) + 6.0 * part, [&] {
-          hipLaunchKernelGGL((k_fused_A<R, N>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, zA, psi.p, Dl.p,
-                             Hl.p, nJ.p, sh.w.p, fa, m, int(m.m3b6 != 0), miT, bm, mm, dfr.p, bufA.p, gpart.p,
-                             h4part.p);
+          if (bitc)   // complex density
+            hipLaunchKernelGGL((k_fused_A<R, N, false, true>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, zA,
+                               psi.p, Dl.p, Hl.p, nJ.p, sh.w.p, fa, m, int(m.m3b6 != 0), miT, bm, mm, dfr.p, bufA.p,
+                               gpart.p, h4part.p);
+          else
+            hipLaunchKernelGGL((k_fused_A<R, N, false, false>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, zA,
+                               psi.p, Dl.p, Hl.p, nJ.p, sh.w.p, fa, m, int(m.m3b6 != 0), miT, bm, mm, dfr.p, bufA.p,
+                               gpart.p, h4part.p);
         });
         K(TC_K_SUM_PARTS, 6.0 * part + 6.0 * fd * nt + 3.0 * fb * nt, [&] {
           hipLaunchKernelGGL((k_sum_parts<R, N>), dim3(nblk(long(nt) * NR)), dim3(256), 0, s, 1, S, nt, t0, 0, nullptr,
@@ -1789,8 +1794,9 @@ struct EngineT : Engine {
           zconv<OP_A1>(s, npair, t0, mi, tb, 1);
         });
         K(TC_K_FUSED_A, fb * ((m.m3b6 ? 9.0 : 5.0) * npair + 8.0 * P + nt) + 6.0 * part, [&] {
-          hipLaunchKernelGGL((k_fused_A<R, N>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, bufB.p, psi.p, Dl.p, Hl.p,
-                             nJ.p, sh.w.p, fa, m, int(m.m3b6 != 0), mi, bm, mm, dfr.p, bufA.p, gpart.p, h4part.p);
+          hipLaunchKernelGGL((k_fused_A<R, N, false, false>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, bufB.p,
+                             psi.p, Dl.p, Hl.p, nJ.p, sh.w.p, fa, m, int(m.m3b6 != 0), mi, bm, mm, dfr.p, bufA.p,
+                             gpart.p, h4part.p);
         });
         K(TC_K_SUM_PARTS, 6.0 * part + 6.0 * fd * nt + 3.0 * fb * nt, [&] {
           hipLaunchKernelGGL((k_sum_parts<R, N>), dim3(nblk(long(nt) * NR)), dim3(256), 0, s, 1, S, nt, t0, 0, nullptr,
@@ -2070,7 +2076,7 @@ struct EngineT : Engine {
             zconv<OP_A1>(s, npair, t0, mi, tb, 1);
           });
           K(TC_K_FUSED_A, fb * ((m.m3b6 ? 9.0 : 5.0) * npair + 8.0 * P + nt) + 6.0 * part, [&] {
-            hipLaunchKernelGGL((k_fused_A<R, N, true>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, bufB.p, PSI[sp],
+            hipLaunchKernelGGL((k_fused_A<R, N, true, false>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, bufB.p, PSI[sp],
                                DL[sp], HL[sp], NJ[sp], W[sp], fa, m, int(m.m3b6 != 0), mi, bm, mm, dfr.p, bufA.p,
                                gpart.p, h4part.p, NJ[o]);
           });

@@ -360,12 +360,6 @@ __device__ __forceinline__ void to_latt(const Basis<R>& B, const cx<R>* S, cx<R>
   for (int d = 0; d < 3; ++d) T[d] = B.b[3 * d] * S[0] + B.b[3 * d + 1] * S[1] + B.b[3 * d + 2] * S[2];
 }
 
-// T_d = sum_e M_de Y_e with the metric M = B B^T (so T = B X for X_c = sum_d B_dc Y_d)
-template <typename R>
-__device__ __forceinline__ void apply_metric(const Basis<R>& M, const cx<R>* Y, cx<R>* T) {
-#pragma unroll
-  for (int d = 0; d < 3; ++d) T[d] = M.b[3 * d] * Y[0] + M.b[3 * d + 1] * Y[1] + M.b[3 * d + 2] * Y[2];
-}
 
 // Lattice components of vector fields: out_d = sum_c B_dc in_c for nvec vectors of N^3 points;
 // component c of vector v at in + v vstride + c cstride (same layout for out).
@@ -933,7 +927,9 @@ k_zconv_mfma(const cx<float>* in, cx<float>* out, long npairs, int t0, MeshInfo 
 //   slot 2: -m3a4 w H3a4_q . X_par = -m3a4 w Hl_q . Y_par     (2 x 3a4)
 //   h4    : w X_par psi_q  (accumulated as w Y_par psi_q, made Cartesian at the end)   (Alg. 3a3)
 // and, if do3b6, writes the 3b6 sources S_s,c = X_s,c n in the forward split form
-// (lattice T_s = B S_s = n M Y_s, M = B B^T) src4 per pair [P_par, R_par, P_anti, R_anti].
+// (lattice T_s = B S_s = M (n Y_s), M = B B^T) src4 per pair [P_par, R_par, P_anti, R_anti].  The metric
+// is applied after the forward transform (it is constant): with U~_e the transform of n Y_s,e,
+// P = sum_e (kappa_1 M_1e + kappa_2 M_2e) U~_e and R = sum_e M_3e U~_e.
 // Delta = k_t - k_q.
 template <typename R, int N>
 struct PassA {
@@ -946,7 +942,9 @@ template <typename R, int N>
 constexpr int kFusedAWaves = (sizeof(R) == 4 && N == 24) ? 3 : 1;
 
 // POL (spin-polarised runs): the antiparallel-channel 3b6 sources take the other spin's density nA.
-template <typename R, int N, bool POL = false>
+// CN: the density is complex (biorthogonal mode, n = sum w conj(chi) psi); otherwise only its real part is
+// read (n = sum w |psi|^2).
+template <typename R, int N, bool POL = false, bool CN = true>
 __global__ void __launch_bounds__((Fz<R, N>::NTH)) __attribute__((amdgpu_waves_per_eu(kFusedAWaves<R, N>)))
 k_fused_A(const cx<R>* buf5, const cx<R>* psi, const cx<R>* Dl, const cx<R>* Hl, const cx<R>* n, const double* w,
           FusedArgs fa, Masks m, int do3b6, MeshInfo mi, Basis<R> B, Basis<R> M, const double* dfr, cx<R>* src4,
@@ -1035,24 +1033,21 @@ k_fused_A(const cx<R>* buf5, const cx<R>* psi, const cx<R>* Dl, const cx<R>* Hl,
             cfma(h4[i][d], wq, Y[d], p);
           }
           if (do3b6) {
-            cx<R> T[3];
-            apply_metric(M, Y, T);
 #pragma unroll
-            for (int d = 0; d < 3; ++d) sm[(1 + d) * PL + so] = T[d] * nk[i];
+            for (int d = 0; d < 3; ++d) sm[(1 + d) * PL + so] = CN ? Y[d] * nk[i] : nk[i].x * Y[d];
           }
         }
         if (anti && do3b6) {
-          cx<R> Y[3], T[3];
-#pragma unroll
-          for (int d = 0; d < 3; ++d) Y[d] = sm[(ab + d) * PL + so];
-          apply_metric(M, Y, T);
           cx<R> nanti;
           if constexpr (POL)
             nanti = na[i];
           else
             nanti = nk[i];
 #pragma unroll
-          for (int d = 0; d < 3; ++d) sm[(ab + d) * PL + so] = T[d] * nanti;
+          for (int d = 0; d < 3; ++d) {
+            const cx<R> y = sm[(ab + d) * PL + so];
+            sm[(ab + d) * PL + so] = CN ? y * nanti : nanti.x * y;
+          }
         }
       }
       // finish this partner's multiply-accumulates here (a compiler-only fence: no instruction), so that
@@ -1071,16 +1066,17 @@ k_fused_A(const cx<R>* buf5, const cx<R>* psi, const cx<R>* Dl, const cx<R>* Hl,
 #pragma unroll
         for (int i = 0; i < KP; ++i) {
           const int so = wg.so0 + RB * F::LD * i;
-          const unsigned o = wg.zo + RB * N * i;
           const R k2 = R(double(mfreq<N>(wg.y0 + RB * i)) + del[1]);
-          if (par) {
-            sto(dst, ob[i], k1 * sm[PL + so] + k2 * sm[2 * PL + so]);
-            sto(dst + NR, ob[i], sm[3 * PL + so]);
-          }
-          if (anti) {
-            sto(dst + 2 * NR, ob[i], k1 * sm[ab * PL + so] + k2 * sm[(ab + 1) * PL + so]);
-            sto(dst + 3 * NR, ob[i], sm[(ab + 2) * PL + so]);
-          }
+          R c[3];   // kappa_1 M_1e + kappa_2 M_2e
+#pragma unroll
+          for (int e = 0; e < 3; ++e) c[e] = k1 * M.b[e] + k2 * M.b[3 + e];
+          auto emit = [&](int slot, cx<R>* d0) {
+            const cx<R> u0 = sm[slot * PL + so], u1 = sm[(slot + 1) * PL + so], u2 = sm[(slot + 2) * PL + so];
+            sto(d0, ob[i], c[0] * u0 + c[1] * u1 + c[2] * u2);
+            sto(d0 + NR, ob[i], M.b[6] * u0 + M.b[7] * u1 + M.b[8] * u2);
+          };
+          if (par) emit(1, dst);
+          if (anti) emit(ab, dst + 2 * NR);
         }
       }
     }
