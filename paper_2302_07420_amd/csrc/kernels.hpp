@@ -1026,12 +1026,17 @@ k_fused_A(const cx<R>* buf5, const cx<R>* psi, const cx<R>* Dl, const cx<R>* Hl,
           cx<R> Y[3];
 #pragma unroll
           for (int d = 0; d < 3; ++d) Y[d] = sm[(1 + d) * PL + so];
+          // the two dot products are summed over d before their weights are applied
+          cx<R> sD = Y[0] * ldo(dq, ob[i]), sH = Y[0] * ldo(hq, ob[i]);
 #pragma unroll
-          for (int d = 0; d < 3; ++d) {
-            cfma(ga[i][1], a1 * wq, Y[d], ldo(dq + long(d) * fa.P * NR, ob[i]));
-            cfma(ga[i][2], a2 * wq, Y[d], ldo(hq + d * NR, ob[i]));
-            cfma(h4[i][d], wq, Y[d], p);
+          for (int d = 1; d < 3; ++d) {
+            sD = sD + Y[d] * ldo(dq + long(d) * fa.P * NR, ob[i]);
+            sH = sH + Y[d] * ldo(hq + d * NR, ob[i]);
           }
+          ga[i][1] = ga[i][1] + (a1 * wq) * sD;
+          ga[i][2] = ga[i][2] + (a2 * wq) * sH;
+#pragma unroll
+          for (int d = 0; d < 3; ++d) cfma(h4[i][d], wq, Y[d], p);
           if (do3b6) {
 #pragma unroll
             for (int d = 0; d < 3; ++d) sm[(1 + d) * PL + so] = CN ? Y[d] * nk[i] : nk[i].x * Y[d];
