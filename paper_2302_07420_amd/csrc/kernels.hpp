@@ -441,6 +441,24 @@ template <typename T>
 __device__ __forceinline__ void sto(T* base, unsigned byteoff, T v) {
   *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + byteoff) = v;
 }
+// A work-group-uniform global pointer, read from the first lane and typed as global memory, so that the
+// loads through it take the scalar-base + 32-bit vector-offset form with no per-lane address arithmetic.
+template <typename T>
+using gptr = const __attribute__((address_space(1))) T*;
+template <typename T>
+__device__ __forceinline__ gptr<T> uniform_global(const T* p) {
+  const unsigned long long v = reinterpret_cast<unsigned long long>(p);
+  const unsigned lo = __builtin_amdgcn_readfirstlane(unsigned(v));
+  const unsigned hi = __builtin_amdgcn_readfirstlane(unsigned(v >> 32));
+  return reinterpret_cast<gptr<T>>((static_cast<unsigned long long>(hi) << 32) | lo);
+}
+template <typename R>
+__device__ __forceinline__ cx<R> ldo(gptr<cx<R>> base, unsigned byteoff) {
+  typedef R v2 __attribute__((ext_vector_type(2)));
+  const v2 v = *reinterpret_cast<const __attribute__((address_space(1))) v2*>(
+      reinterpret_cast<const __attribute__((address_space(1))) char*>(base) + byteoff);
+  return mk<R>(v.x, v.y);
+}
 
 // Logical work-group index from the hardware one.  Work-groups are dealt to the 8 XCDs round-robin;
 // this map gives each XCD a contiguous range of logical indices (bijective for any grid size).
@@ -973,7 +991,7 @@ k_fused_A(const cx<R>* buf5, const cx<R>* psi, const cx<R>* Dl, const cx<R>* Hl,
   // the next partner's five pair planes are loaded into registers while this partner is transformed
   cx<R> pre[5][KP];
   auto fetch = [&](int q) {
-    const cx<R>* src = buf5 + (long(wg.t) * fa.P + q) * 5 * NR;
+    const gptr<cx<R>> src = uniform_global(buf5 + (long(wg.t) * fa.P + q) * 5 * NR);
 #pragma unroll
     for (int f = 0; f < 5; ++f)
 #pragma unroll
@@ -986,9 +1004,9 @@ k_fused_A(const cx<R>* buf5, const cx<R>* psi, const cx<R>* Dl, const cx<R>* Hl,
     const double* del = dfr + 3 * pair_dindex(mi, jt, q, 1);
     const R k1 = R(double(mfreq<N>(wg.x)) + del[0]);
     const cx<R>* src = buf5 + pair * 5 * NR;
-    const cx<R>* pq = psi + long(q) * NR;
-    const cx<R>* dq = Dl + long(q) * NR;          // component d at dq + d P N^3
-    const cx<R>* hq = Hl + long(q) * 3 * NR;      // component d at hq + d N^3
+    const gptr<cx<R>> pq = uniform_global(psi + long(q) * NR);
+    const gptr<cx<R>> dq = uniform_global(Dl + long(q) * NR);       // component d at dq + d P N^3
+    const gptr<cx<R>> hq = uniform_global(Hl + long(q) * 3 * NR);   // component d at hq + d N^3
 #pragma unroll 1
     for (int g = 0; g < (SPLIT ? 2 : 1); ++g) {
       const bool par = !SPLIT || g == 0, anti = !SPLIT || g == 1;
