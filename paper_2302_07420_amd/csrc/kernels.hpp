@@ -529,9 +529,12 @@ __global__ void __launch_bounds__((Fz<R, N>::NTH)) k_pair_xy(const cx<R>* bra, c
 // m3b5 conj(Hl_qd) psi_t, with Zl = B (m2bx2 D_j - m3b3 h1 psi_j + m3b4 h4_j) and Hl = B conj(H3b)
 // (TC mode: chi = psi and H3b = conj(H3a4), so Hl = B H3a4); forward xy transformed:
 // out[(pair 2 + 0)] = kappa_1 T~_1 + kappa_2 T~_2, out[(pair 2 + 1)] = T~_3, pair = t P + q, Delta = k_t - k_q.
-// occupancy target: 3 waves per SIMD where that costs no spills (FP32 at 24^3)
+// FP32 at 24^3: no register prefetch of the partner fields, 4 waves per SIMD instead (no spills); elsewhere
+// the prefetch
 template <typename R, int N>
-constexpr int kPassBWaves = (sizeof(R) == 4 && N == 24) ? 3 : 1;
+constexpr bool kPassBPrefetch = !(sizeof(R) == 4 && N == 24);
+template <typename R, int N>
+constexpr int kPassBWaves = kPassBPrefetch<R, N> ? 1 : 4;
 
 template <typename R, int N>
 __global__ void __launch_bounds__((Fz<R, N>::NTH)) __attribute__((amdgpu_waves_per_eu(kPassBWaves<R, N>)))
@@ -556,7 +559,9 @@ k_passB_xy(const cx<R>* psi, const cx<R>* chi, const cx<R>* Zl, const cx<R>* Hl,
       for (int d = 0; d < 3; ++d) zt[i][d] = zb[d * NR + r];
     }
   }
-  // partner fields chi_q, Hl_q of the next round are loaded while this round is transformed
+  // partner fields chi_q, Hl_q of the next round are loaded while this round is transformed (kPassBPrefetch;
+  // otherwise at the start of the round)
+  constexpr bool PF = kPassBPrefetch<R, N>;
   cx<R> pre[NPQ][4][KP];
   auto fetch = [&](int q0) {
 #pragma unroll
@@ -573,9 +578,10 @@ k_passB_xy(const cx<R>* psi, const cx<R>* chi, const cx<R>* Zl, const cx<R>* Hl,
       }
     }
   };
-  if (wg.qb < wg.qe) fetch(wg.qb);
+  if (PF && wg.qb < wg.qe) fetch(wg.qb);
   for (int q0 = wg.qb; q0 < wg.qe; q0 += NPQ) {
     const int nq = min(NPQ, wg.qe - q0);
+    if (!PF) fetch(q0);
 #pragma unroll
     for (int a = 0; a < NPQ; ++a) {
       if (a >= nq) continue;
@@ -589,7 +595,7 @@ k_passB_xy(const cx<R>* psi, const cx<R>* chi, const cx<R>* Zl, const cx<R>* Hl,
         }
       }
     }
-    if (q0 + NPQ < wg.qe) fetch(q0 + NPQ);
+    if (PF && q0 + NPQ < wg.qe) fetch(q0 + NPQ);
     __syncthreads();
     planes_fft<R, N, -1>(sm, 3 * nq, threadIdx.x);
     for (int a = 0; a < nq; ++a) {
