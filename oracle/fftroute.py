@@ -30,13 +30,18 @@ Readings where the paper is silent or garbled:
       grid satisfies N_i/2 >= 2 max|m_i| + 1.
   R3  The 1/Omega carried by FT[chi* phi](0) is kept in every divergence
       correction (the paper's equations drop Omega factors, Sec. 2.6.1).
-  R4  In the G = G' = 0 corrections of 3a2 and 3b6 the short-range part of u
-      enters twice: the finite Q -> 0 remainder of Q^2 u~(Q)^2 =
-      (4 pi A / Q^2 + u~_short)(4 pi A + Q^2 u~_short) is 2 (4 pi A) u~_short(0);
-      Eqs. divcor_3a2_first and 3b6_div_scf1 keep one of the two cross terms.
-      Pinned by the band form (Eq. 3b6_div_band1, no u~_short): on the electron gas
-      the band-k operator tends to the mesh operator as k approaches a mesh point only
-      with this value.
+  R4  The mesh corrections come in two readings (``reading``):
+      "printed" (default): the coefficients as printed.  The G = G' = 0
+      corrections of 3a2 and 3b6 (Eqs. divcor_3a2_first, 3b6_div_scf1) carry one
+      u~_short(0)/N_k, and 2bx1 has no mesh correction (the vector sum of
+      Eq. correction_nabla vanishes on the mesh).
+      "limit": the mesh operator is the limit of the band operator as a band
+      k-point approaches a mesh point.  The G = G' = 0 corrections then carry
+      2 u~_short(0)/N_k, the full finite Q -> 0 remainder of
+      Q^2 u~(Q)^2 = (4 pi A / Q^2 + u~_short)(4 pi A + Q^2 u~_short); and 2bx1 gains
+      the isotropic remainder -(4 pi A_par / N_k) sum_mu f_mu rho~_{mu j}(0) phi_mu
+      that (nabla + ik) leaves on the partner's Bloch phase at the singular point.
+      Both limits are pinned by the band forms on the CPU (tests of the band oracle).
   R13 For a band k-point the vector sum of Eq. correction_nabla is taken at the
       arguments k - q + G of the kernel it replaces (printed with q + G, which is zero
       on the mesh).
@@ -120,7 +125,7 @@ class Problem:
     """
 
     def __init__(self, w, A=None, C=None, coeff=None, left=None, div_correction=True,
-                 alpha=None, biorthogonalize=True):
+                 alpha=None, biorthogonalize=True, reading="printed"):
         self.w = w
         self.lattice = np.asarray(w.lattice, dtype=np.float64)
         self.omega = abs(float(np.linalg.det(self.lattice)))
@@ -141,6 +146,11 @@ class Problem:
         self.nr = int(np.prod(self.grid))
         self.alpha = float(w.alpha if alpha is None else alpha)
         self.div = bool(div_correction)
+        if reading not in ("printed", "limit"):
+            raise ValueError("reading must be 'printed' or 'limit'")
+        self.reading = reading
+        # u~_short(0)/N_k count in the G = G' = 0 corrections of 3a2 and 3b6 (reading R4)
+        self.ushort_mult = 1.0 if reading == "printed" else 2.0
         self.A = torch.as_tensor(w.A if A is None else A, dtype=RD)
         self.C = torch.as_tensor(w.C if C is None else C, dtype=RD)
         ms = [np.fft.fftfreq(N, 1.0 / N).astype(np.int64) for N in self.grid]
@@ -459,7 +469,24 @@ class Problem:
         g = self._exchange_loop(s, body)
         if self.div and self.nkb:
             g = g + self._band_corr(s, self.c_2bx1_band)
+        if self.div and self.reading == "limit":
+            g = g + self.c_2bx1_mesh(s)
         return g
+
+    def c_2bx1_mesh(self, s):
+        """Reading R4 "limit": the remainder -(4 pi A_par / N_k) sum_mu f rho~_{mu j}(0) phi_mu of a mesh
+        target j (the band operator's limit at a mesh point; zero rows for band targets)."""
+        o = self.orb[s]
+        out = []
+        for j in range(self.P):
+            if not self.is_target(j) or self.is_band(j):
+                out.append(torch.zeros_like(o["phi"][0]))
+                continue
+            Q = self.sel(s, o["k"][j])
+            r0 = self.rho0(torch.conj(o["chi"][Q]), o["phi"][j][None])
+            out.append(-FOURPI * self.A[0] / self.nk
+                       * torch.sum((o["f"][Q] * r0)[:, None, None, None] * o["phi"][Q], 0))
+        return torch.stack(out)
 
     def _band_corr(self, s, fn):
         """Stack fn(s, j) over the band targets (zeros elsewhere)."""
@@ -525,7 +552,7 @@ class Problem:
         o2 = self.orb[s2]
         A, C = self.A[ch], self.C[ch]
         ushort = -FOURPI * A * C * C                                   # Eq. u_short
-        c1 = FOURPI * A * (FOURPI * A * self.delta_gb + 2.0 * ushort / self.nk)   # reading R4
+        c1 = FOURPI * A * (FOURPI * A * self.delta_gb + self.ushort_mult * ushort / self.nk)   # R4
         _, _, utH = self.kern(np.zeros(3), "H", ch)
         out = 0
         for q1 in self.sel(s2, o2["k"][q2]):
@@ -759,7 +786,8 @@ class Problem:
                 nG = self.nG[s1]
                 if not band:
                     ushort = -FOURPI * A * C * C
-                    c1 = 2.0 * math.pi * A * (FOURPI * A * self.delta_gb + 2.0 * ushort / self.nk)   # R4
+                    c1 = 2.0 * math.pi * A * (FOURPI * A * self.delta_gb
+                                              + self.ushort_mult * ushort / self.nk)   # R4
                     field = self.IFT(utH * nG)
                 else:
                     # Eqs. 3b6_div_band1-3: band GB bracket without alpha and u_short; the G' != 0 and

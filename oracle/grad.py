@@ -21,20 +21,21 @@ import torch
 from .fftroute import Problem, ALL_TERMS, RD, CD, biorthogonalize_coeffs
 
 
-def energy_and_grad(w, terms=ALL_TERMS, div_correction=True, with_kinetic=True):
+def energy_and_grad(w, terms=ALL_TERMS, div_correction=True, with_kinetic=True, reading="printed"):
     coeff = [torch.as_tensor(c, dtype=CD).clone().requires_grad_(True) for c in w.right]
     A = torch.as_tensor(w.A, dtype=RD).clone().requires_grad_(True)
     C = torch.as_tensor(w.C, dtype=RD).clone().requires_grad_(True)
-    pr = Problem(w, A=A, C=C, coeff=coeff, div_correction=div_correction)
+    pr = Problem(w, A=A, C=C, coeff=coeff, div_correction=div_correction, reading=reading)
     E = pr.energy(terms=terms, with_kinetic=with_kinetic)
     gc = torch.autograd.grad(E, coeff + [A, C])
     return float(E.detach()), [g.detach().numpy() for g in gc[:-2]], gc[-2].numpy(), gc[-1].numpy()
 
 
-def energy(w, coeff=None, A=None, C=None, terms=ALL_TERMS, div_correction=True, with_kinetic=True):
+def energy(w, coeff=None, A=None, C=None, terms=ALL_TERMS, div_correction=True, with_kinetic=True,
+           reading="printed"):
     with torch.no_grad():
         pr = Problem(w, A=A, C=C, coeff=None if coeff is None else [torch.as_tensor(c, dtype=CD) for c in coeff],
-                     div_correction=div_correction)
+                     div_correction=div_correction, reading=reading)
         return float(pr.energy(terms=terms, with_kinetic=with_kinetic))
 
 
@@ -45,13 +46,14 @@ def bitc_pair(w):
     return [c.numpy() for c in cr], [c.numpy() for c in cl]
 
 
-def energy_and_grad_bitc(w, right, left, terms=ALL_TERMS, div_correction=True):
+def energy_and_grad_bitc(w, right, left, terms=ALL_TERMS, div_correction=True, reading="printed"):
     """(E, grad_right, grad_left, dA, dC) of the biorthogonal-mode energy at the given pair."""
     r = [torch.as_tensor(c, dtype=CD).clone().requires_grad_(True) for c in right]
     l = [torch.as_tensor(c, dtype=CD).clone().requires_grad_(True) for c in left]
     A = torch.as_tensor(w.A, dtype=RD).clone().requires_grad_(True)
     C = torch.as_tensor(w.C, dtype=RD).clone().requires_grad_(True)
-    pr = Problem(w, A=A, C=C, coeff=r, left=l, div_correction=div_correction, biorthogonalize=False)
+    pr = Problem(w, A=A, C=C, coeff=r, left=l, div_correction=div_correction, biorthogonalize=False,
+                 reading=reading)
     E = pr.energy(terms=terms)
     g = torch.autograd.grad(E, r + l + [A, C])
     nk = len(r)
@@ -59,9 +61,9 @@ def energy_and_grad_bitc(w, right, left, terms=ALL_TERMS, div_correction=True):
             g[-2].numpy(), g[-1].numpy())
 
 
-def energy_bitc(w, right, left, terms=ALL_TERMS, div_correction=True):
+def energy_bitc(w, right, left, terms=ALL_TERMS, div_correction=True, reading="printed"):
     with torch.no_grad():
         pr = Problem(w, coeff=[torch.as_tensor(c, dtype=CD) for c in right],
                      left=[torch.as_tensor(c, dtype=CD) for c in left], div_correction=div_correction,
-                     biorthogonalize=False)
+                     biorthogonalize=False, reading=reading)
         return float(pr.energy(terms=terms))

@@ -62,12 +62,21 @@ def gb_delta(lattice, kmesh, alpha):
     return omega / (4.0 * math.sqrt(math.pi ** 3 * alpha)) - (-alpha + tot) / nk
 
 
-def heg_terms(w, A=None, C=None, alpha=None, div_correction=True):
+def heg_terms(w, A=None, C=None, alpha=None, div_correction=True, reading="printed"):
     """Diagonal eigenvalue of every printed term for every occupied plane wave.
 
     Returns (eps, momenta, weights) with eps[term] an array over orbitals of one
-    spin channel (both channels are equal for unpolarized input).
+    spin channel (both channels are equal for unpolarized input).  Bands of zero
+    filling are targets of every term and partners of none; a target's divergence
+    corrections take the filling of the occupied plane wave of the same momentum
+    (FT[phi*_mu phi_j](0) = delta_{p_mu, p_j}/Omega).  ``reading``
+    selects the mesh corrections as in the FFT-route oracle: "printed" (one
+    u~_short(0)/N_k in the G = G' = 0 corrections of 3a2 and 3b6, no 2bx1 mesh
+    correction) or "limit" (two, and the 2bx1 remainder -(4 pi A_par / N_k) f_j / Omega).
     """
+    if reading not in ("printed", "limit"):
+        raise ValueError("reading must be 'printed' or 'limit'")
+    um = 1.0 if reading == "printed" else 2.0
     lat = np.asarray(w.lattice, dtype=np.float64)
     B = 2.0 * math.pi * np.linalg.inv(lat).T
     omega = abs(np.linalg.det(lat))
@@ -93,7 +102,9 @@ def heg_terms(w, A=None, C=None, alpha=None, div_correction=True):
     nbar = np.sum(wq) / omega                       # per-spin density
     ushort = -FOURPI * A * C * C
     D = p[:, None, :] - p[None, :, :]              # D[j,q] = p_j - p_q
-    off = ~np.eye(P, dtype=bool)
+    same = np.sum(D * D, -1) < 1e-20                # pairs of one plane wave (Q = 0)
+    off = ~same
+    fs = (same * f[None, :]).sum(1)                 # filling of the occupied plane wave of p_j
     K = [_kern(D.reshape(-1, 3), A[s], C[s]) for s in range(2)]
     ut = [k[0].reshape(P, P) for k in K]
     lap = [k[1].reshape(P, P) for k in K]
@@ -103,20 +114,22 @@ def heg_terms(w, A=None, C=None, alpha=None, div_correction=True):
     eps = {t: np.zeros(P) for t in ("2ah", "2bh1", "2bh2", "2ax", "2bx1", "2bx2", "3a1", "3a2", "3a3",
                                       "3a4", "3b1", "3b2", "3b3", "3b4", "3b5", "3b6")}
     # 2ax: -(1/Omega) sum_q w_q V2a(p_j - p_q) (Q = 0 row keeps L(0)-W(0)) + GB
-    eps["2ax"] = -(V2a * wq[None, :]).sum(1) / omega - FOURPI * dgb * f / omega
+    eps["2ax"] = -(V2a * wq[None, :]).sum(1) / omega - FOURPI * dgb * fs / omega
     # 2bx1 / 2bx2
     dot_q = np.einsum("jqa,qa->jq", D, p)
     dot_j = np.einsum("jqa,ja->jq", D, p)
     eps["2bx1"] = (wq[None, :] * ut[0] * dot_q * off).sum(1) / omega
     eps["2bx2"] = -(wq[None, :] * ut[0] * dot_j * off).sum(1) / omega
+    if div_correction and reading == "limit":
+        eps["2bx1"] = eps["2bx1"] - FOURPI * A[0] / nk * fs / omega
     # 3a2: h5^{s,s2}(q2) = sum_{q1 != q2} w_q1 P^2 u~^2 / Omega^2 + corrections; both spins s2
     Dn2 = np.sum(D * D, -1)
     h6 = 0.0
     for s in (0, 1):                 # channel of (target spin, spin of q1 and q2)
         h5 = (wq[:, None] * Dn2 * ut[s] ** 2 * off).sum(0) / omega ** 2     # index q2 (sum over q1)
         if div_correction:
-            c1 = FOURPI * A[s] * (FOURPI * A[s] * dgb + 2.0 * ushort[s] / nk)   # reading R4
-            h5 = h5 + c1 * f / omega ** 2
+            c1 = FOURPI * A[s] * (FOURPI * A[s] * dgb + um * ushort[s] / nk)   # reading R4
+            h5 = h5 + c1 * fs / omega ** 2
         h6 += np.sum(wq * h5)
     eps["3a2"] = np.full(P, 0.5 * h6)
     # vector sums a(q2) = (i/Omega) sum_{q1 != q2} w_q1 (p_q2 - p_q1) u~(p_q2 - p_q1)
@@ -131,8 +144,8 @@ def heg_terms(w, A=None, C=None, alpha=None, div_correction=True):
     for s in (0, 1):                # channel of (spin of the density, target spin)
         b6 = b6 + 0.5 * (wq[None, :] * Dn2 * ut[s] ** 2 * off).sum(1) * nbar / omega
         if div_correction:
-            c1 = 2.0 * math.pi * A[s] * (FOURPI * A[s] * dgb + 2.0 * ushort[s] / nk)   # reading R4
-            b6 = b6 + c1 * (1.0 / omega) * nbar * f
+            c1 = 2.0 * math.pi * A[s] * (FOURPI * A[s] * dgb + um * ushort[s] / nk)   # reading R4
+            b6 = b6 + c1 * (1.0 / omega) * nbar * fs
     eps["3b6"] = b6
     return eps, p, f
 

@@ -39,10 +39,11 @@ def _kinetic_diag(w, k):
     return 0.5 * np.sum(kg * kg, 1)
 
 
-def operator_matrices(w, right, left=None, terms=ALL_TERMS):
+def operator_matrices(w, right, left=None, terms=ALL_TERMS, reading="printed"):
     """[T + h[phi]] on each k-point's plane-wave set, H[k][G', G] = <e_G'| T + h |e_G>.
 
-    ``right``/``left``: per k (nb, npw) arrays, used as given (left already biorthonormal, or None).
+    ``right``/``left``: per k (nb, npw) arrays, used as given (left already biorthonormal, or None);
+    ``reading``: the mesh corrections' reading of the FFT-route oracle (R4).
     """
     nk = w.nk
     npw = [m.shape[0] for m in w.miller]
@@ -56,7 +57,7 @@ def operator_matrices(w, right, left=None, terms=ALL_TERMS):
             ext_l.append(np.concatenate([left[k], E]))
         occ.append(np.concatenate([np.asarray(w.occ[k], dtype=np.float64), np.zeros(nx)]))
     wx = w.replace(right=ext_r, left=ext_l if left is not None else None, occ=occ)
-    pr = Problem(wx, biorthogonalize=False)
+    pr = Problem(wx, biorthogonalize=False, reading=reading)
     g = sum(MULT.get(t, 1) * pr.term(t, 0) for t in terms)
     hc = pr.to_coeff(g)
     nb = right[0].shape[0]

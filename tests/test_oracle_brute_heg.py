@@ -42,22 +42,23 @@ def test_fftroute_equals_literal_permutation_integrals(w):
                 assert np.max(np.abs(g - ref)) <= 1e-11 * np.max(np.abs(ref)), (t, name)
 
 
-def test_electron_gas_gamma_every_term_closed_form():
+@pytest.mark.parametrize("reading", ["printed", "limit"])
+def test_electron_gas_gamma_every_term_closed_form(reading):
     w = T.workload("heg14_g16")
-    E, parts = Problem(w).energy(per_term=True)
-    Eh, ph = heg_energy(w)
+    E, parts = Problem(w, reading=reading).energy(per_term=True)
+    Eh, ph = heg_energy(w, reading=reading)
     for k, v in ph.items():
         assert float(parts[k]) == pytest.approx(v, abs=1e-12 * max(1.0, abs(Eh))), k
     assert float(E) == pytest.approx(Eh, rel=1e-12)
 
 
-def test_electron_gas_twists_operator_is_diagonal_and_matches():
-    # 2x1x1 twists, the 5 lowest |k+G|^2 plane waves per twist, partially filled
-    w = T.heg_twist(rs=2.0, nelec=10, tw=1, grid=12, ecut=4.0, nocc=5)
+@pytest.mark.parametrize("reading", ["printed", "limit"])
+def test_electron_gas_twists_operator_is_diagonal_and_matches(reading):
+    # 2x2x2 twists, the 3 lowest |k+G|^2 plane waves per twist, partially filled
     w = T.heg_twist(rs=2.0, nelec=10, tw=2, grid=12, ecut=3.0, nocc=3)
     w = w.replace(occ=[np.array([1.0, 0.8, 0.5]) for _ in w.occ])
-    pr = Problem(w)
-    eps, p, f = heg_terms(w)
+    pr = Problem(w, reading=reading)
+    eps, p, f = heg_terms(w, reading=reading)
     for t in eps:
         g = pr.term(t, 0)
         for j in range(pr.P):

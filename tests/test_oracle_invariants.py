@@ -6,7 +6,7 @@ import pytest
 import torch
 
 import tcinputs as T
-from oracle.fftroute import Problem, TERMS2, TERMS3, MULT
+from oracle.fftroute import ALL_TERMS, MULT, Problem, TERMS2, TERMS3
 
 
 def _fold_to_supercell(w):
@@ -128,3 +128,22 @@ def test_target_sample_rows_equal_full_rows():
         a, b = full.term(t, 0), part.term(t, 0)
         for j in (1, 6):
             assert torch.max(torch.abs(b[j] - a[j])) <= 1e-14 * torch.max(torch.abs(a)), (t, j)
+
+
+@pytest.mark.parametrize("left_mix", [None, 0.15])
+def test_coefficient_output_obeys_parseval(left_mix):
+    """Pins to_coeff against the real-space bracket: for every orbital, <chi_p|g_p> over the cell (grid
+    sum, Sec. 2.2's periodic transform not involved) equals sum_G conj(c~_p(G)) (Hc)_p(G) on its plane-wave
+    set, with c~ the left coefficients (the right ones in TC mode).  A wrong sqrt(Omega) or 1/N_r in the
+    coefficient output, or a misplaced gather, breaks it."""
+    w = T.tiny_fcc(kmesh=(2, 1, 1), grid=8, ecut=2.0, nb=2, a=6.0, occ=[1.0, 0.7], left_mix=left_mix)
+    pr = Problem(w)
+    g = sum(MULT.get(t, 1) * pr.term(t, 0) for t in ALL_TERMS)
+    hc = pr.to_coeff(g)
+    bra = pr.braket(0, g)
+    cl = pr.cr if pr.cl is None else pr.cl
+    for ik in range(pr.nk):
+        J = pr.sel(0, ik)
+        lhs = torch.sum(torch.conj(cl[ik]) * hc[ik], 1)
+        assert torch.max(torch.abs(lhs - bra[J])) <= 1e-13 * torch.max(torch.abs(bra))
+    assert float(torch.max(torch.abs(bra))) > 1e-3

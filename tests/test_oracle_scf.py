@@ -33,3 +33,25 @@ def test_operator_matrix_of_plane_waves_is_diagonal(heg2):
     H = S.operator_matrices(heg2, heg2.right)[0]
     off = H - np.diag(np.diag(H))
     assert np.abs(off).max() < 1e-12 * np.abs(H).max()
+
+
+@pytest.mark.parametrize("reading", ["printed", "limit"])
+def test_operator_matrix_diagonal_is_the_closed_form(heg2, reading):
+    """Pins the coefficient-space output of the FFT-route oracle (to_coeff: sqrt(Omega), 1/N_r and the
+    plane-wave gather): every diagonal element of [T + h] on the plane-wave set equals |p|^2/2 plus the
+    closed-form eigenvalue of that plane wave as a zero-filling target (O3, no grid and no FFT)."""
+    from oracle.fftroute import MULT
+    from oracle.heg import heg_terms
+
+    H = S.operator_matrices(heg2, heg2.right, reading=reading)[0]
+    npw = heg2.miller[0].shape[0]
+    E = np.eye(npw, dtype=np.complex128)
+    wx = heg2.replace(right=[np.concatenate([heg2.right[0], E])],
+                      occ=[np.concatenate([np.asarray(heg2.occ[0], float), np.zeros(npw)])])
+    eps, p, f = heg_terms(wx, reading=reading)
+    nb = heg2.right[0].shape[0]
+    lam = sum(MULT.get(t, 1) * e for t, e in eps.items())[nb:]
+    ref = 0.5 * np.sum(p[nb:] ** 2, 1) + lam
+    assert np.abs(np.diag(H) - ref).max() < 1e-12 * np.abs(ref).max()
+    # the closed forms differ between the plane waves, so a wrong scale of any entry shows
+    assert np.ptp(ref.real) > 1e-2 * np.abs(ref).max()
