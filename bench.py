@@ -151,7 +151,25 @@ def cpu_baseline(budget_s: float):
         "sample": f"fcc a=10.26 bohr cell, 24^3 grid, 4 bands, 2x2x2 k-mesh ({npairs} same-spin pairs, all terms, "
                   f"both spins, energy {E:.10f} Ha); {dt:.1f} s",
         "seconds": dt,
+        "energy_Ha": E,
+        "_workload": w,
     }
+
+
+def energy_errors_vs_oracle(w, E_oracle, stream):
+    """The TC energy of the oracle's sample from the GPU path in each precision, and its relative error
+    against the oracle's FP64 energy of the same inputs."""
+    import paper_2302_07420_amd as tc
+
+    out = {"workload": w.name, "oracle_energy_Ha": E_oracle}
+    for name, prec in (("fp32", tc.TC_PREC_FP32), ("fp32_splitbf16", tc.TC_PREC_FP32_SPLITBF16),
+                       ("fp64", tc.TC_PREC_FP64)):
+        op, keep = make_op(w, prec, stream)
+        E = op.energy()[0]
+        op.close()
+        del keep
+        out[name] = {"energy_Ha": E, "rel_err": abs(E - E_oracle) / abs(E_oracle)}
+    return out
 
 
 def main():
@@ -334,6 +352,12 @@ def main():
             log(f"cpu oracle: {cpu['value']:.3f} pairs/s on {cpu['cores']} threads ({cpu['seconds']:.1f} s)")
         except Exception as e:  # the baseline is reported, never required
             log(f"cpu baseline failed: {e!r}")
+    vs_oracle = None
+    if cpu is not None:
+        wo = cpu.pop("_workload")
+        vs_oracle = energy_errors_vs_oracle(wo, cpu["energy_Ha"], stream)
+        log("energy vs oracle on its sample: " + ", ".join(
+            f"{k} {v['rel_err']:.2e}" for k, v in vs_oracle.items() if isinstance(v, dict)))
 
     res = {
         "metric": METRIC,
@@ -358,6 +382,8 @@ def main():
         },
         "energy_Ha": E32,
         "energy_rel_err_fp32_vs_fp64": (abs(E32 - fp64["energy_Ha"]) / abs(fp64["energy_Ha"])) if fp64 else None,
+        "energy_rel_err_vs_oracle": vs_oracle["fp32"]["rel_err"] if vs_oracle else None,
+        "energy_vs_oracle": vs_oracle,
         "fp64_gpu": fp64,
         "speedup_fp32_vs_fp64_gpu": (w.npairs / (ms32 / 1e3)) / fp64["value"] if fp64 else None,
         "fp32_splitbf16_gpu": dict(split, energy_rel_err_vs_fp64=(abs(split["energy_Ha"] - fp64["energy_Ha"])

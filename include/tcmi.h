@@ -76,6 +76,16 @@ enum {
   TC_T_ALL = (1 << 17) - 1
 };
 
+/* div_correction values of tc_set_options.
+ * TC_DIV_PRINTED: the SCF-mesh corrections as printed: the G = G' = 0 corrections of 3a2 and 3b6
+ *   (Eqs. divcor_3a2_first, 3b6_div_scf1) carry one u~_short(0)/N_k (Eq. u_short), and 2bx1 has none.
+ * TC_DIV_LIMIT: the mesh operator taken as the limit of the band operator at a mesh point: two
+ *   u~_short(0)/N_k in those corrections (the whole finite Q -> 0 remainder of Q^2 u~(Q)^2), and on
+ *   2bx1 the remainder -(4 pi A_par / N_k) sum_mu f_mu FT[chi*_mu phi_j](0) phi_mu that the gradient
+ *   leaves on the partner's Bloch phase (mu over the target's k-point).
+ * The band forms (band k-points) are the same in both. */
+enum { TC_DIV_OFF = 0, TC_DIV_PRINTED = 1, TC_DIV_LIMIT = 2 };
+
 /* Energy breakdown written by tc_energy (hartree per cell, both spins). */
 enum {
   TC_E_KINETIC = 0,   /* sum f <chi|-lap/2|phi> / N_k (chi = phi in TC mode)             */
@@ -120,8 +130,9 @@ int tc_set_jastrow(tc_ctx* ctx, const double A[2], const double C[2]);
 /* precision: TC_PREC_FP64, TC_PREC_FP32 or TC_PREC_FP32_SPLITBF16 (FFT butterflies,
  * pair products and kernel multiplies in that precision; corrections, overlaps,
  * partner sums across chunks and energy reductions always FP64).
- * alpha: exponent of the auxiliary function exp(-alpha q^2)/q^2 of Eq. aux (bohr^2, > 0).  div_correction: 0/1.
- * term_mask: OR of TC_T_* bits. */
+ * alpha: exponent of the auxiliary function exp(-alpha q^2)/q^2 of Eq. aux (bohr^2, > 0).
+ * div_correction: one of TC_DIV_* (the divergence corrections of Sec. 2.5 and their reading).
+ * term_mask: OR of TC_T_* bits.  TC_ERR_ARG for any other precision or div_correction value. */
 int tc_set_options(tc_ctx* ctx, int precision, double alpha, int div_correction, uint64_t term_mask);
 
 /* Copy the occupied orbitals of k-point ik to the device: `right` holds nband x

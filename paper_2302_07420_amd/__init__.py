@@ -18,6 +18,11 @@ LIBPATH = os.path.join(HERE, "libtcmi.so")
 TC_PREC_FP64 = 0
 TC_PREC_FP32 = 1
 TC_PREC_FP32_SPLITBF16 = 2
+# div_correction codes of tc_set_options (readings of the mesh divergence corrections)
+TC_DIV_OFF = 0
+TC_DIV_PRINTED = 1
+TC_DIV_LIMIT = 2
+_READINGS = {"printed": TC_DIV_PRINTED, "limit": TC_DIV_LIMIT}
 
 TERM_BITS = {
     "2ah": 1 << 0, "2bh1": 1 << 1, "2bh2": 1 << 2, "2ax": 1 << 3, "2bx1": 1 << 4, "2bx2": 1 << 5,
@@ -159,9 +164,14 @@ class TCOperator:
         c = np.ascontiguousarray(np.asarray(C, dtype=np.float64))
         self._check(self._L.tc_set_jastrow(self._h, _dp(a), _dp(c)), "tc_set_jastrow")
 
-    def set_options(self, precision=TC_PREC_FP64, alpha=1.0, div_correction=True, terms=TERM_ALL):
-        self._check(self._L.tc_set_options(self._h, int(precision), float(alpha), int(bool(div_correction)),
-                                           int(terms)), "tc_set_options")
+    def set_options(self, precision=TC_PREC_FP64, alpha=1.0, div_correction=True, terms=TERM_ALL,
+                    reading="printed"):
+        """div_correction on/off; reading "printed" (TC_DIV_PRINTED) or "limit" (TC_DIV_LIMIT)."""
+        if reading not in _READINGS:
+            raise ValueError("reading must be 'printed' or 'limit'")
+        code = _READINGS[reading] if div_correction else TC_DIV_OFF
+        self._check(self._L.tc_set_options(self._h, int(precision), float(alpha), code, int(terms)),
+                    "tc_set_options")
 
     def set_nspin(self, nspin: int):
         """1: both spin channels hold the same orbitals; 2: spin-polarised TC mode (load spin 1 separately)."""
@@ -364,7 +374,8 @@ class TCOperator:
 
 
 def from_workload(w, precision=TC_PREC_FP64, terms=TERM_ALL, div_correction=True, device=0, A=None, C=None,
-                  coeff=None, stream=None, batch=0, left=None, symmetry=None, pair_store=True) -> TCOperator:
+                  coeff=None, stream=None, batch=0, left=None, symmetry=None, pair_store=True,
+                  reading="printed") -> TCOperator:
     """Build an operator from a ``tcinputs.Workload``: TC mode, or the biorthogonal mode when the workload
     (or ``left``) holds left orbitals; ``symmetry``: crystal operations [(R, tau)] (see set_symmetry)."""
     op = TCOperator(device, stream)
@@ -378,7 +389,7 @@ def from_workload(w, precision=TC_PREC_FP64, terms=TERM_ALL, div_correction=True
     for ik, m in enumerate(w.miller):
         op.set_basis(ik, m)
     op.set_jastrow(w.A if A is None else A, w.C if C is None else C)
-    op.set_options(precision, w.alpha, div_correction, terms)
+    op.set_options(precision, w.alpha, div_correction, terms, reading)
     if symmetry:
         op.set_symmetry(symmetry)
     cs = w.right if coeff is None else coeff
@@ -403,11 +414,21 @@ def energy_function():
     [nk, nband, npw_max] (rows zero-padded like tc_apply_all), ``A`` and ``C`` float64
     tensors of shape (2,), ``occ`` a float64 array [nk, nband].  Forward loads the
     coefficients and Jastrow parameters into ``op`` and returns the energy (float64
-    scalar); backward calls tc_energy_backward_dev, whose gradient convention
+    scalar); backward loads the same inputs again (the op may hold others by then) and
+    calls tc_energy_backward_dev, whose gradient convention
     (dE/dRe c + i dE/dIm c) is the one torch uses for complex leaves.  Only argument
     marshalling happens here; the energy and its gradient are computed by the library.
     """
     import torch
+
+    def load(op, coeff, A, C, occ):
+        nk, nb, npw_max = coeff.shape
+        op.set_jastrow(A.detach().cpu().numpy(), C.detach().cpu().numpy())
+        packed = [coeff[k, :, : op.npw[k]].contiguous() for k in range(nk)]   # [nband][npw(k)] rows
+        torch.cuda.current_stream().synchronize()
+        for k in range(nk):
+            op.load_orbitals_dev(k, packed[k].data_ptr(), nb, occ[k])
+        op.sync()
 
     class TCEnergy(torch.autograd.Function):
         @staticmethod
@@ -417,29 +438,25 @@ def energy_function():
             nk, nb, npw_max = coeff.shape
             if npw_max != op.npw_max or nk != len(op.npw):
                 raise TCError("coeff shape does not match the operator's k-mesh and basis")
-            op.set_jastrow(A.detach().cpu().numpy(), C.detach().cpu().numpy())
             occ = np.asarray(occ, dtype=np.float64).reshape(nk, nb)
-            packed = [coeff[k, :, : op.npw[k]].contiguous() for k in range(nk)]   # [nband][npw(k)] rows
-            torch.cuda.current_stream().synchronize()
-            for k in range(nk):
-                op.load_orbitals_dev(k, packed[k].data_ptr(), nb, occ[k])
-            op.sync()
-            del packed
+            load(op, coeff, A, C, occ)
             e, _ = op.energy()
             ctx.op = op
-            ctx.shape = coeff.shape
-            ctx.dev = coeff.device
-            ctx.save_for_backward(coeff)     # kept alive: the library reads it again in backward
+            ctx.occ = occ
+            ctx.save_for_backward(coeff.detach(), A.detach(), C.detach())
             return torch.tensor(e, dtype=torch.float64)
 
         @staticmethod
         def backward(ctx, gE):
-            (coeff,) = ctx.saved_tensors
-            grad = torch.zeros(ctx.shape, dtype=torch.complex128, device=ctx.dev)
+            # the op may have been loaded with other inputs since this forward (a second forward, gradcheck):
+            # load this forward's coefficients and Jastrow parameters again before the gradient
+            coeff, A, C = ctx.saved_tensors
+            load(ctx.op, coeff, A, C, ctx.occ)
+            grad = torch.zeros(coeff.shape, dtype=torch.complex128, device=coeff.device)
             torch.cuda.current_stream().synchronize()
             dA, dC = ctx.op.backward_dev(grad.data_ptr())
             g = float(gE)
-            return (None, grad * g, torch.as_tensor(dA * g, dtype=torch.float64),
-                    torch.as_tensor(dC * g, dtype=torch.float64), None)
+            return (None, grad * g, torch.as_tensor(dA * g, dtype=torch.float64, device=A.device),
+                    torch.as_tensor(dC * g, dtype=torch.float64, device=C.device), None)
 
     return TCEnergy

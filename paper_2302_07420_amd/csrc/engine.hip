@@ -157,6 +157,8 @@ struct Problem {
   int prec = TC_PREC_FP64;
   double alpha = 1.0;
   int div = 1;
+  int reading = TC_DIV_PRINTED;           // TC_DIV_PRINTED or TC_DIV_LIMIT (coefficients of the mesh corrections)
+  bool force_rem = false;                 // 2bx1 remainder on while the gradient application masks 2bx1 off
   uint64_t mask = TC_T_ALL;
   bool options = false;
   int nb = 0;
@@ -810,6 +812,22 @@ Masks make_masks(uint64_t m) {
   return k;
 }
 
+// Reading TC_DIV_LIMIT: whether the mesh targets get the 2bx1 remainder (selected 2bx1, or the gradient
+// application, which masks the grad-u . grad convolutions off but keeps every Hermitian correction).
+inline bool rem_2bx1(const Problem& pb) {
+  return pb.reading == TC_DIV_LIMIT && ((pb.mask & TC_T_2BX1) || pb.force_rem);
+}
+
+// 2ax correction bracket and 2bx1 remainder in one coefficient: both are -4 pi c sum_mu f rho~_{mu j}(0) phi_mu
+// (Eq. divcorr_2ax_scf with c = Delta_GB; the remainder with c = A_par / N_k).
+inline double dgb_eff(const Problem& pb, const Masks& m, double a_par) {
+  return m.m2ax * pb.delta_gb + (rem_2bx1(pb) ? a_par / pb.nk : 0.0);
+}
+
+inline bool need_corr(const Problem& pb, const Masks& m) {
+  return pb.div && (pb.mask & TC_T_CORR) && (m.m2ax || m.m3a2 || m.m3b6 || rem_2bx1(pb));
+}
+
 struct Events {
   std::vector<hipEvent_t> e;
   explicit Events(int n) : e(n, nullptr) {
@@ -1005,14 +1023,15 @@ struct EngineT : Engine {
     TC_HIP(hipMemcpy(tHU.p, HU.data(), NR * sizeof(R), hipMemcpyHostToDevice));
     TC_HIP(hipMemcpy(tHu0.p, hu0.data(), NR * sizeof(double), hipMemcpyHostToDevice));
     TC_HIP(hipMemcpy(tHu1.p, hu1.data(), NR * sizeof(double), hipMemcpyHostToDevice));
-    // correction prefactors: A (Eqs. divcor_3a2_second, 3b6_div_scf2/3) and
-    // A [4 pi A Delta_GB + 2 u~_short(0)/N_k] with u~_short(0) = -4 pi A C^2 (Eqs. u_short, divcor_3a2_first,
-    // 3b6_div_scf1).  The factor 2: the finite Q -> 0 remainder of Q^2 u~(Q)^2 holds both cross terms of
-    // (4 pi A/Q^2 + u~_short)(4 pi A + Q^2 u~_short).
+    // correction prefactors: A (Eqs. divcor_3a2_second, 3b6_div_scf2/3; the 2bx1 remainder of TC_DIV_LIMIT) and
+    // A [4 pi A Delta_GB + nu u~_short(0)/N_k] with u~_short(0) = -4 pi A C^2 (Eqs. u_short, divcor_3a2_first,
+    // 3b6_div_scf1): nu = 1 as printed; nu = 2 for TC_DIV_LIMIT, where the finite Q -> 0 remainder of
+    // Q^2 u~(Q)^2 holds both cross terms of (4 pi A/Q^2 + u~_short)(4 pi A + Q^2 u~_short).
+    const double nu = pb.reading == TC_DIV_LIMIT ? 2.0 : 1.0;
     for (int ch = 0; ch < 2; ++ch) {
       corrA[ch] = chan_eval(tv, pb.A, pb.C, ch, [](auto A, auto) { return A; });
       corrB[ch] = chan_eval(tv, pb.A, pb.C, ch, [&](auto A, auto C) {
-        return A * (kFourPi * A * pb.delta_gb - 2.0 * kFourPi * A * C * C / double(pb.nk));
+        return A * (kFourPi * A * pb.delta_gb - nu * kFourPi * A * C * C / double(pb.nk));
       });
     }
   }
@@ -1546,8 +1565,7 @@ struct EngineT : Engine {
                            sh.npw.p, nb, pb.npw_max, sh.tkin.p);
         TC_HIP(hipMemsetAsync(sh.ecorr.p, 0, size_t(2) * P * sizeof(double), s));
       }
-      if (pb.div && (pb.mask & TC_T_CORR) && (m.m2ax || m.m3a2 || m.m3b6) && !(ts && ts->band))
-        corrections(s, sh, pb, m, ts);
+      if (need_corr(pb, m) && !(ts && ts->band)) corrections(s, sh, pb, m, ts);
     });
     TC_HIP(hipEventRecord(ev.e[5], s));
     TC_HIP(hipEventSynchronize(ev.e[5]));
@@ -1879,7 +1897,7 @@ struct EngineT : Engine {
       hipLaunchKernelGGL(k_kinetic, dim3(P), dim3(256), 0, s, sh.coef.p, sh.coef.p, sh.kg.p, sh.npw.p, nb, npm,
                          sh.tkin.p);
       TC_HIP(hipMemsetAsync(sh.ecorr.p, 0, size_t(2) * P * sizeof(double), s));
-      if (pb.div && (pb.mask & TC_T_CORR) && (m.m2ax || m.m3a2 || m.m3b6)) corrections(s, sh, pb, m, nullptr);
+      if (need_corr(pb, m)) corrections(s, sh, pb, m, nullptr);
     });
     TC_HIP(hipEventRecord(ev.e[5], s));
     TC_HIP(hipEventSynchronize(ev.e[5]));
@@ -2156,7 +2174,7 @@ struct EngineT : Engine {
         hipLaunchKernelGGL(k_kinetic, dim3(P), dim3(256), 0, s, sh.coef.p + sp * cofs, sh.coef.p + sp * cofs, sh.kg.p,
                            sh.npw.p, nb, npm, sh.tkin.p + size_t(sp) * P);
       TC_HIP(hipMemsetAsync(sh.ecorr.p, 0, size_t(4) * P * sizeof(double), s));
-      if (pb.div && (pb.mask & TC_T_CORR) && (m.m2ax || m.m3a2 || m.m3b6)) corrections_pol(s, sh, pb, m);
+      if (need_corr(pb, m)) corrections_pol(s, sh, pb, m);
     });
     TC_HIP(hipEventRecord(ev.e[5], s));
     TC_HIP(hipEventSynchronize(ev.e[5]));
@@ -2245,7 +2263,8 @@ struct EngineT : Engine {
       const double const1 = c1a_p * cs[sp] + c1a_a * cs[o];
       const double c1sn0 = c1s_p * n0[sp] + c1s_a * n0[o];
       hipLaunchKernelGGL(k_corr_apply, dim3(nblk(long(P) * npm)), dim3(256), 0, s, cf, cf, Ssp, sh.O.p, Zg, Wg,
-                         focc.p + sp * P, sh.npw.p, nb, nb, npm, P, pb.omega, m.m2ax, pb.delta_gb, m.m3a2, const1, 0.0,
+                         focc.p + sp * P, sh.npw.p, nb, nb, npm, P, pb.omega, 1.0, dgb_eff(pb, m, corrA[0]), m.m3a2,
+                         const1, 0.0,
                          m.m3b6, c1sn0, 0.0, sh.dhc2.p + sp * cofs, sh.dhc3.p + sp * cofs);
       hipLaunchKernelGGL(k_corr_add, dim3(P), dim3(256), 0, s, cf, sh.dhc2.p + sp * cofs, sh.dhc3.p + sp * cofs,
                          sh.npw.p, nb, npm, sh.out.p + sp * cofs, sh.ecorr.p + size_t(2) * sp * P);
@@ -2325,8 +2344,8 @@ struct EngineT : Engine {
         }
     if (!ts) {
       hipLaunchKernelGGL(k_corr_apply, dim3(nblk(long(P) * pb.npw_max)), dim3(256), 0, s, sh.coef.p, sh.coef.p,
-                         sh.S.p, sh.O.p, sh.Zg.p, sh.Wg.p, focc.p, sh.npw.p, nb, nb, pb.npw_max, P, pb.omega, m.m2ax,
-                         pb.delta_gb, m.m3a2, const1, const1i, m.m3b6, c1s * n0, c1s * n0i, sh.dhc2.p, sh.dhc3.p);
+                         sh.S.p, sh.O.p, sh.Zg.p, sh.Wg.p, focc.p, sh.npw.p, nb, nb, pb.npw_max, P, pb.omega, 1.0,
+                         dgb_eff(pb, m, corrA[0]), m.m3a2, const1, const1i, m.m3b6, c1s * n0, c1s * n0i, sh.dhc2.p, sh.dhc3.p);
       hipLaunchKernelGGL(k_corr_add, dim3(P), dim3(256), 0, s, cl, sh.dhc2.p, sh.dhc3.p, sh.npw.p, nb, pb.npw_max,
                          sh.out.p, sh.ecorr.p);
       return;
@@ -2359,8 +2378,8 @@ struct EngineT : Engine {
     hipLaunchKernelGGL(k_overlap, dim3(nk * nb * nv), dim3(256), 0, s, cl, nb, sh.ZgT.p, nv, sh.npw.p, pb.npw_max, nk,
                        sh.OT.p);
     hipLaunchKernelGGL(k_corr_apply, dim3(nblk(long(NT) * pb.npw_max)), dim3(256), 0, s, ts->coef, sh.coef.p, sh.ST.p,
-                       sh.OT.p, sh.Zg.p, sh.WgT.p, focc.p, sh.npw.p, nb, nv, pb.npw_max, NT, pb.omega, m.m2ax,
-                       pb.delta_gb, m.m3a2, const1, const1i, m.m3b6, c1s * n0, c1s * n0i, sh.dhc2T.p, sh.dhc3T.p);
+                       sh.OT.p, sh.Zg.p, sh.WgT.p, focc.p, sh.npw.p, nb, nv, pb.npw_max, NT, pb.omega, 1.0,
+                       dgb_eff(pb, m, corrA[0]), m.m3a2, const1, const1i, m.m3b6, c1s * n0, c1s * n0i, sh.dhc2T.p, sh.dhc3T.p);
     hipLaunchKernelGGL(k_corr_add, dim3(NT), dim3(256), 0, s, ts->coef, sh.dhc2T.p, sh.dhc3T.p, sh.npw.p, nv,
                        pb.npw_max, ts->out, sh.ecorrT.p);
   }
@@ -2622,7 +2641,8 @@ void band_corrections_host(tc_ctx* c, const Masks& m, const std::vector<double>&
   double c1a = 0, c1b_unit = 0;
   for (int ch = 0; ch < 2; ++ch) {
     const double A = pb.A[ch], Cc = pb.C[ch];
-    c1a += kFourPi * A * (kFourPi * A * pb.delta_gb - 2.0 * kFourPi * A * Cc * Cc / pb.nk);   // reading R4
+    const double nu = pb.reading == TC_DIV_LIMIT ? 2.0 : 1.0;   // u~_short(0)/N_k count of Eq. divcor_3a2_first
+    c1a += kFourPi * A * (kFourPi * A * pb.delta_gb - nu * kFourPi * A * Cc * Cc / pb.nk);
     c1b_unit += 2.0 * kPi * A * kFourPi * A;   // times Delta_GB^band (Eq. 3b6_div_band1)
   }
   const double const1 = c1a * cs;
@@ -3303,6 +3323,7 @@ int do_backward(tc_ctx* c, void* grad_dev, double* grad_host, double* dA, double
         std::swap(c->sh.coef.n, c->sh.coefL.n);
       }
       c->pb.negate_b = false;
+      c->pb.force_rem = false;
       c->pb.mask = mask;
       c->tables_dirty = true;   // the next application rebuilds the operator's tables
       c->e_total = e;
@@ -3329,11 +3350,13 @@ int do_backward(tc_ctx* c, void* grad_dev, double* grad_host, double* dA, double
   if (!pb.bitc) {
     if (grad_dev || grad_host) {
       pb.mask = m & ~kTermsB;
+      pb.force_rem = (m & TC_T_2BX1) != 0;   // the 2bx1 remainder is Hermitian: it stays in the gradient
       c->tables_dirty = true;
       c->eng->upload_tables(pb, TableVariant{TableVariant::GRADIENT, 0, 0.0});
       run_apply(c, nullptr, nullptr);
       finish(4.0, grad_dev, grad_host);
       pb.mask = m;
+      pb.force_rem = false;
     }
   } else {
     // E = Re sum f <chi| T + h2/2 + h3/3 |phi> with the pair held fixed:
@@ -3789,10 +3812,13 @@ int tc_set_options(tc_ctx* c, int precision, double alpha, int div_correction, u
     if (precision != TC_PREC_FP64 && precision != TC_PREC_FP32 && precision != TC_PREC_FP32_SPLITBF16)
       return fail(c, TC_ERR_ARG, "unknown precision");
     if (!(alpha > 0.0)) return fail(c, TC_ERR_ARG, "alpha must be > 0");
+    if (div_correction != TC_DIV_OFF && div_correction != TC_DIV_PRINTED && div_correction != TC_DIV_LIMIT)
+      return fail(c, TC_ERR_ARG, "div_correction must be TC_DIV_OFF, TC_DIV_PRINTED or TC_DIV_LIMIT");
     Problem& pb = c->pb;
     pb.prec = precision;
     pb.alpha = alpha;
-    pb.div = div_correction ? 1 : 0;
+    pb.div = div_correction != TC_DIV_OFF;
+    pb.reading = div_correction == TC_DIV_LIMIT ? TC_DIV_LIMIT : TC_DIV_PRINTED;
     pb.mask = term_mask & TC_T_ALL;
     pb.options = true;
     c->tables_dirty = true;

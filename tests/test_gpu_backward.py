@@ -167,3 +167,59 @@ def test_torch_autograd_function():
     assert err < 1e-10
     assert np.abs(A.grad.numpy() - gA).max() < 1e-10 * np.abs(gA).max()
     assert np.abs(C.grad.numpy() - gC).max() < 1e-10 * np.abs(gC).max()
+
+
+def test_torch_autograd_two_forwards_before_backward():
+    """E(c1) + E(c2) on one op: each backward must use its own forward's inputs (the op holds c2 and the
+    second A, C when the first term's backward runs).  Gradients against the oracle for each input."""
+    import torch
+
+    w = CASES["fcc_k211_g8_partial"]()
+    w2 = T.perturbed_start(w, 0.3, 5)
+    A2 = (w.A[0] * 1.1, w.A[1] * 0.9)
+    ref1 = OG.energy_and_grad(w)
+    ref2 = OG.energy_and_grad(w2.replace(A=A2))
+    _say("[gpu] torch.autograd.Function: two forwards on one op before backward")
+    op = tc.from_workload(w, precision=tc.TC_PREC_FP64)
+    npw_max = op.npw_max
+    TCEnergy = tc.energy_function()
+    leaves = []
+    for ww, AA in ((w, w.A), (w2, A2)):
+        c = np.zeros((ww.nk, ww.right[0].shape[0], npw_max), dtype=np.complex128)
+        for k in range(ww.nk):
+            c[k, :, : ww.right[k].shape[1]] = ww.right[k]
+        leaves.append((torch.tensor(c, device="cuda", requires_grad=True),
+                       torch.tensor(AA, dtype=torch.float64, requires_grad=True),
+                       torch.tensor(ww.C, dtype=torch.float64, requires_grad=True)))
+    e1 = TCEnergy.apply(op, *leaves[0], np.array(w.occ))
+    e2 = TCEnergy.apply(op, *leaves[1], np.array(w2.occ))
+    (e1 + e2).backward()
+    op.close()
+    for (coeff, A, C), (E, gc, gA, gC), e in zip(leaves, (ref1, ref2), (e1, e2)):
+        assert float(e.detach()) == pytest.approx(E, rel=1e-12)
+        g = coeff.grad.cpu().numpy()
+        scale = max(np.abs(x).max() for x in gc)
+        err = max(np.abs(g[k, :, : gc[k].shape[1]] - gc[k]).max() for k in range(len(gc))) / scale
+        assert err < 1e-10, err
+        assert A.grad.device == A.device
+        assert np.abs(A.grad.numpy() - gA).max() < 1e-10 * np.abs(gA).max()
+        assert np.abs(C.grad.numpy() - gC).max() < 1e-10 * np.abs(gC).max()
+
+
+def test_gradient_limit_reading_matches_oracle():
+    """The 2bx1 remainder of the limit reading is Hermitian: it stays in the gradient application while the
+    grad-u . grad convolutions are switched off."""
+    w = CASES["fcc_k211_g8_partial"]()
+    E, gc, gA, gC = OG.energy_and_grad(w, reading="limit")
+    _say("[gpu] backward fcc_k211 fp64 reading=limit vs oracle autograd")
+    op = tc.from_workload(w, precision=tc.TC_PREC_FP64, reading="limit")
+    Eg, _ = op.energy()
+    g, dA, dC = op.backward()
+    op.close()
+    scale = max(np.abs(x).max() for x in gc)
+    err = max(np.abs(a - b).max() for a, b in zip(g, gc)) / scale
+    perr = max(np.abs(dA - gA).max(), np.abs(dC - gC).max()) / max(np.abs(gA).max(), np.abs(gC).max())
+    _say(f"    E {Eg} vs {E}; grad rel err {err:.3e}; param rel err {perr:.3e}")
+    assert abs(Eg - E) < 1e-10 * abs(E)
+    assert err < 1e-10
+    assert perr < 1e-10

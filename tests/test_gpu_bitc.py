@@ -239,3 +239,25 @@ def test_biorthogonal_gradients_vs_oracle(case, prec):
     assert E2 == E1
     assert er < tol and el < tol
     assert ep < (1e-10 if prec == "fp64" else 1e-6)
+
+
+def test_limit_reading_bitc_operator_and_gradients_fp64():
+    """The limit reading in the biorthogonal mode: operator and energy against the oracle, and both
+    gradients (the 2bx1 remainder and the u~_short terms enter the left operator as their adjoints)."""
+    from oracle import grad as OG
+    w = CASES["fcc_k211_g8_bitc"]()
+    pr = Problem(w, reading="limit")
+    tot = [c.numpy() for c in pr.to_coeff(sum(MULT.get(t, 1) * pr.term(t, 0) for t in ALL_TERMS))]
+    r, l = OG.bitc_pair(w)
+    Eo, gr0, gl0, dA0, dC0 = OG.energy_and_grad_bitc(w, r, l, reading="limit")
+    _say("[gpu] bitc fcc_k211 fp64 reading=limit: operator, energy, right/left gradients")
+    op = tc.from_workload(w, precision=tc.TC_PREC_FP64, reading="limit")
+    hc = op.apply()
+    E1, _ = op.energy()
+    gr, gl, dA, dC = op.backward_lr()
+    op.close()
+    assert relerr(hc, tot) < FP64_TOL
+    assert abs(E1 - Eo) < FP64_TOL * abs(Eo)
+    assert relerr(gr, gr0) < 1e-10 and relerr(gl, gl0) < 1e-10
+    ps = max(np.abs(dA0).max(), np.abs(dC0).max())
+    assert max(np.abs(dA - dA0).max(), np.abs(dC - dC0).max()) < 1e-10 * ps

@@ -9,7 +9,12 @@ checks what it can compute independently:
     those targets, for every term whose oracle cost does not grow with the
     number of orbital pairs (all but 3a2, 3a4, 3b2, 3b5);
   * the terms left out there through a property that holds at any size: the
-    three-body block <phi_i|h3|phi_j> is Hermitian, and the V2a block too.
+    three-body block <phi_i|h3|phi_j> is Hermitian, and the V2a block too;
+  * the bench cell and grid on a 2x2x2 k-mesh (32 orbitals, 1,024 pairs, 24^3; the
+    oracle takes about 15 s): every term alone and all terms together, element by
+    element, in FP64, FP32 and split BF16, with the pair store on and off and with
+    batches whose last one is partial;
+  * a small problem on the 48^3 grid: all terms, element by element, in FP64 and FP32.
 """
 import numpy as np
 import pytest
@@ -135,3 +140,80 @@ def test_bench_workload_fp32_matches_fp64_every_element():
     _say(f"    max element difference / max |h c| = {err:.3e}; energies {out['fp32'][1]!r} {out['fp64'][1]!r}")
     assert err < FP32_TOL
     assert abs(out["fp32"][1] - out["fp64"][1]) < 1e-6 * abs(out["fp64"][1])
+
+
+ALL = PAIR_FREE + ("3a2", "3a4", "3b2", "3b5")
+SPLIT_TOL = 2e-5
+
+
+@pytest.fixture(scope="module")
+def fcc_k222_g24():
+    """The bench cell, grid, bands and Jastrow on a 2x2x2 k-mesh; the oracle's output per term."""
+    w = T.fcc_si(kmesh=(2, 2, 2))
+    _say("[oracle] fcc_si_x1_k2x2x2_g24: every term (FP64 CPU)")
+    pr = Problem(w)
+    per = {t: [c.numpy() for c in pr.to_coeff(MULT.get(t, 1) * pr.term(t, 0))] for t in ALL}
+    tot = [sum(per[t][k] for t in ALL) for k in range(w.nk)]
+    return w, per, tot, float(pr.energy())
+
+
+def test_bench_grid_every_term_fp64(fcc_k222_g24):
+    w, per, tot, E = fcc_k222_g24
+    scale = max(np.abs(x).max() for x in tot)
+    for t in ALL:
+        _say(f"[gpu] fcc_si k222 24^3 fp64 term {t} alone")
+        op = tc.from_workload(w, precision=tc.TC_PREC_FP64, terms=_mask((t,)))
+        hc = op.apply()
+        op.close()
+        err = max(np.abs(a - b).max() for a, b in zip(hc, per[t])) / scale
+        assert err < FP64_TOL, (t, err)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "split"])
+@pytest.mark.parametrize("batch,store", [(0, True), (5, True), (5, False)])
+def test_bench_grid_all_terms(fcc_k222_g24, prec, batch, store):
+    """All terms at the bench grid through the bench's kernels (24-point plane kernels, the resident pair
+    store, the shared 3b6 / pass-B z stage); batch 5 of 32 targets leaves a partial last batch."""
+    w, per, tot, E = fcc_k222_g24
+    P = {"fp64": tc.TC_PREC_FP64, "fp32": tc.TC_PREC_FP32, "split": tc.TC_PREC_FP32_SPLITBF16}[prec]
+    tol = {"fp64": FP64_TOL, "fp32": FP32_TOL, "split": SPLIT_TOL}[prec]
+    _say(f"[gpu] fcc_si k222 24^3 {prec} all terms batch={batch} pair_store={store}")
+    op = tc.from_workload(w, precision=P, batch=batch, pair_store=store)
+    hc = op.apply()
+    Eg, _ = op.energy()
+    op.close()
+    scale = max(np.abs(x).max() for x in tot)
+    err = max(np.abs(a - b).max() for a, b in zip(hc, tot)) / scale
+    eerr = abs(Eg - E) / abs(E)
+    _say(f"    max element error / max |h c| = {err:.3e}; energy {Eg!r} vs oracle {E!r} (rel {eerr:.3e})")
+    assert err < tol
+    assert eerr < (FP64_TOL if prec == "fp64" else 1e-6)
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", FP64_TOL), ("fp32", FP32_TOL)])
+def test_grid_48_all_terms(prec, tol):
+    """48-point plane kernels (FP64: spin channels in separate LDS rounds) against the oracle."""
+    w = T.tiny_fcc(kmesh=(2, 1, 1), grid=48, ecut=3.0, nb=2, a=7.0, occ=[1.0, 0.7])
+    _say(f"[gpu] tiny fcc 48^3 {prec}: all terms vs oracle")
+    pr = Problem(w)
+    per = {t: [c.numpy() for c in pr.to_coeff(MULT.get(t, 1) * pr.term(t, 0))] for t in ALL}
+    tot = [sum(per[t][k] for t in ALL) for k in range(w.nk)]
+    E = float(pr.energy())
+    op = tc.from_workload(w, precision=tc.TC_PREC_FP64 if prec == "fp64" else tc.TC_PREC_FP32)
+    hc = op.apply()
+    Eg, _ = op.energy()
+    op.close()
+    scale = max(np.abs(x).max() for x in tot)
+    err = max(np.abs(a - b).max() for a, b in zip(hc, tot)) / scale
+    _say(f"    max element error / max |h c| = {err:.3e}; energy rel err {abs(Eg - E) / abs(E):.3e}")
+    assert err < tol
+    assert abs(Eg - E) < (FP64_TOL if prec == "fp64" else 1e-6) * abs(E)
+    if prec == "fp64":
+        scale = max(np.abs(x).max() for x in tot)
+        for t in ("3a2", "3a4", "3b2", "3b5", "3b6"):
+            op = tc.from_workload(w, precision=tc.TC_PREC_FP64, terms=_mask((t,)))
+            hc = op.apply()
+            op.close()
+            e = max(np.abs(a - b).max() for a, b in zip(hc, per[t])) / scale
+            _say(f"    term {t}: {e:.3e}")
+            assert e < FP64_TOL, (t, e)

@@ -203,3 +203,44 @@ def test_pair_store_switch_on_a_live_context(case):
     for hc in runs:
         assert relerr(hc, tot) < FP64_TOL
     assert relerr(runs[1], runs[0]) < 1e-13 and relerr(runs[2], runs[0]) < 1e-15
+
+
+@pytest.mark.parametrize("reading", ["printed", "limit"])
+def test_reading_of_the_mesh_corrections_fp64(case, reading):
+    """Both readings of the mesh corrections (TC_DIV_PRINTED: one u~_short(0)/N_k in the G = G' = 0 corrections
+    of 3a2 and 3b6, no 2bx1 correction; TC_DIV_LIMIT: two, and the 2bx1 remainder), term by term and in
+    total, against the oracle under the same reading."""
+    name, w, _ = case
+    pr = Problem(w, reading=reading)
+    for t in ("2bx1", "3a2", "3b6", "2ax"):
+        _say(f"[gpu] {name} fp64 reading={reading} term {t}")
+        ref = [c.numpy() for c in pr.to_coeff(MULT.get(t, 1) * pr.term(t, 0))]
+        op = tc.from_workload(w, precision=tc.TC_PREC_FP64, terms=tc.TERM_BITS[t] | tc.TERM_BITS["corr"],
+                              reading=reading)
+        hc = op.apply()
+        op.close()
+        assert relerr(hc, ref) < FP64_TOL, (t, relerr(hc, ref))
+    _say(f"[gpu] {name} fp64 reading={reading} all terms + energy")
+    tot = [c.numpy() for c in pr.to_coeff(sum(MULT.get(t, 1) * pr.term(t, 0) for t in ALL_TERMS))]
+    E = float(pr.energy())
+    op = tc.from_workload(w, precision=tc.TC_PREC_FP64, reading=reading)
+    hc = op.apply()
+    Eg, _ = op.energy()
+    op.close()
+    assert relerr(hc, tot) < FP64_TOL
+    assert abs(Eg - E) < FP64_TOL * abs(E)
+
+
+def test_readings_differ_and_bad_code_is_rejected():
+    w = CASES["fcc_k211_g8_partial"]()
+    _say("[gpu] fcc_k211 fp64 printed vs limit energies; invalid div_correction code")
+    es = []
+    for reading in ("printed", "limit"):
+        op = tc.from_workload(w, precision=tc.TC_PREC_FP64, reading=reading)
+        es.append(op.energy()[0])
+        op.close()
+    assert abs(es[0] - es[1]) > 1e-6 * abs(es[0])
+    op = tc.TCOperator(0)
+    with pytest.raises(tc.TCError, match="status -1"):
+        op._check(op._L.tc_set_options(op._h, 0, 1.0, 3, tc.TERM_ALL), "tc_set_options")
+    op.close()
