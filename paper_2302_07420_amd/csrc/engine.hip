@@ -1093,6 +1093,11 @@ struct EngineT : Engine {
         return;
       }
     }
+    if constexpr (N == 48) {   // each column on a lane pair
+      hipLaunchKernelGGL((k_zconv48<R, OP>), dim3(nblk(2 * npair * N * N)), dim3(256), 0, s, in, out, npair, t0, mi,
+                         tb, sign, inB);
+      return;
+    }
     hipLaunchKernelGGL((k_zconv<R, N, OP>), dim3(nblk(npair * N * N)), dim3(256), 0, s, in, out, npair, t0, mi, tb,
                        sign, inB);
   }

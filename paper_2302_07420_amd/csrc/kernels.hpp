@@ -387,10 +387,13 @@ __device__ __forceinline__ void cfma(cx<R>& acc, R a, cx<R> u, cx<R> v) {   // a
 
 // Work-group layout of the plane kernels: RB rows x N columns of threads; thread (y0, x) owns the
 // plane points (y0 + RB i, x), i < N/RB, so loads and stores are coalesced along x and need no index
-// division, and in each transform pass it owns one line of one plane (up to RB planes per pass).
+// division.  Transforms of N <= 32 give each thread one line of one plane per pass (up to RB planes per
+// pass); at N = 48 (COMB) the lines are split into their 3 x 16 prime-factor combs (planes_comb48).
 template <typename R, int N>
 struct Fz {
-  static constexpr int RB = (N % 8 == 0) ? 8 : 4;
+  // 48 points: 16 rows (768 threads, 12 waves on the one work-group that the LDS planes leave room for
+  // per CU, 3 owned points per thread)
+  static constexpr int RB = N == 48 ? 16 : (N % 8 == 0) ? 8 : 4;
   static constexpr int NTH = RB * N;
   static constexpr int KP = N / RB;
   static constexpr int LD = N + 1;
@@ -399,14 +402,104 @@ struct Fz {
   static constexpr bool fits(int planes) { return planes * PLANE * int(sizeof(cx<R>)) <= kLdsMax; }
   static constexpr int kFitPlanes = kLdsMax / (PLANE * int(sizeof(cx<R>)));
   static constexpr int GRP = kFitPlanes < RB ? kFitPlanes : RB;   // one-plane-per-partner rounds
+  static constexpr bool COMB = N == 48;                    // comb transforms, outputs in sigma order
+  static constexpr bool PREFETCH = N < 48;                 // next partner's planes loaded into registers
 };
+
+// Position of index k after the in-place comb transform of a 48-point axis (planes_comb48): the
+// Good-Thomas map stores sub-index (k1, k2) = (k mod 3, k mod 16) at 16 k1 + 3 k2 (mod 48).
+__device__ __forceinline__ int sigma48(int k) {
+  const int r = 16 * (k % 3) + 3 * (k & 15);
+  return r >= 48 ? r - 48 : r;
+}
+
+// In-place 2D transform of np 48 x 48 planes in LDS ([np][48][49]) in three passes over the
+// prime-factor (Good-Thomas) structure 48 = 3 x 16, which has no twiddles between its factors:
+//   1. every row: the three 16-point transforms over n2 of its combs n1 (positions 16 n1 + 3 n2 mod 48);
+//   2. every column: the same along y;
+//   3. every (k2x, k2y): the 3 x 3 transform over (n1x, n1y).
+// Each pass writes back to the positions it read, so sub-index (a, b) stays at 16 a + 3 b (mod 48).
+// With the input index in natural order (the Ruritanian map n = 16 n1 + 3 n2) the output index is the
+// Chinese-remainder map k = 16 k1 + 33 k2, so output k sits at sigma48(k) on each axis; with the input
+// at sigma48 positions the output is in natural order (the two maps swap roles).  A thread holds one
+// 16-point comb (32 registers in FP32) instead of a 48-point line.  Ends with a barrier.
+template <typename R, int DIR>
+__device__ __forceinline__ void planes_comb48(cx<R>* sm, int np, int tid, int nth) {
+  constexpr int N = 48, LD = N + 1, PL = N * LD;
+  for (int t = tid; t < np * N; t += nth) {
+    const int p = t / N, y = t - p * N;
+    cx<R>* row = sm + p * PL + y * LD;
+#pragma unroll
+    for (int n1 = 0; n1 < 3; ++n1) {
+      cx<R> v[16];
+#pragma unroll
+      for (int n2 = 0; n2 < 16; ++n2) v[n2] = row[(16 * n1 + 3 * n2) % N];
+      fft_pow2<R, 16, DIR>(v);
+#pragma unroll
+      for (int n2 = 0; n2 < 16; ++n2) row[(16 * n1 + 3 * n2) % N] = v[n2];
+      __builtin_amdgcn_sched_barrier(0);   // one comb in registers at a time
+    }
+  }
+  __syncthreads();
+  for (int t = tid; t < np * N; t += nth) {
+    const int p = t / N, x = t - p * N;
+    cx<R>* col = sm + p * PL + x;
+#pragma unroll
+    for (int n1 = 0; n1 < 3; ++n1) {
+      cx<R> v[16];
+#pragma unroll
+      for (int n2 = 0; n2 < 16; ++n2) v[n2] = col[((16 * n1 + 3 * n2) % N) * LD];
+      fft_pow2<R, 16, DIR>(v);
+#pragma unroll
+      for (int n2 = 0; n2 < 16; ++n2) col[((16 * n1 + 3 * n2) % N) * LD] = v[n2];
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+  __syncthreads();
+  for (int t = tid; t < np * 256; t += nth) {
+    const int p = t >> 8, ky = (t >> 4) & 15, kx = t & 15;
+    cx<R>* pl = sm + p * PL;
+    int xo[3], yo[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const int xa = 16 * a + 3 * kx, ya = 16 * a + 3 * ky;
+      xo[a] = xa >= N ? xa - N : xa;
+      yo[a] = (ya >= N ? ya - N : ya) * LD;
+    }
+    cx<R> v[3][3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int b = 0; b < 3; ++b) v[a][b] = pl[yo[a] + xo[b]];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) dft3<R, DIR>(v[a]);
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      cx<R> c[3] = {v[0][b], v[1][b], v[2][b]};
+      dft3<R, DIR>(c);
+#pragma unroll
+      for (int a = 0; a < 3; ++a) v[a][b] = c[a];
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int b = 0; b < 3; ++b) pl[yo[a] + xo[b]] = v[a][b];
+  }
+  __syncthreads();
+}
 
 // in-place 2D transform of np planes in LDS ([np][N][N+1]); thread row p takes planes p, p + RB, ...;
 // ends with a barrier.  The plane kernels below write and read LDS outside these transforms only at the
-// points each thread owns (so0 + RB LD i), so a round's reads after a transform and the next round's
-// writes need no barrier between them: only the barrier before the next transform.
+// points each thread owns (PlaneWG::so, natural order), so a round's reads after a transform and the next
+// round's writes need no barrier between them: only the barrier before the next transform.  At N = 48
+// the transform is planes_comb48: reads after it use PlaneWG::ss (sigma order), and a barrier separates
+// them from the next round's writes (end_round).
 template <typename R, int N, int DIR>
 __device__ __forceinline__ void planes_fft(cx<R>* sm, int np, int tid) {
+  if constexpr (Fz<R, N>::COMB) {
+    planes_comb48<R, DIR>(sm, np, tid, Fz<R, N>::NTH);
+    return;
+  }
   constexpr int LD = N + 1, RB = Fz<R, N>::RB;
   const int p0 = tid / N, l = tid - (tid / N) * N;
   for (int p = p0; p < np; p += RB) {
@@ -472,11 +565,12 @@ __device__ __forceinline__ int xcd_major(int b, int n) {
 // share its L2
 template <typename R, int N>
 struct PlaneWG {
+  using F = Fz<R, N>;
   int x, y0, c, z, t, qb, qe;
   unsigned zo;   // offset of owned point i within a volume: zo + RB N i
   int so0;       // LDS offset of owned point i: so0 + RB LD i
+  int sx;        // column of owned points after a comb transform (sigma48(x); N = 48 only)
   __device__ PlaneWG(const FusedArgs& fa) {
-    using F = Fz<R, N>;
     const int tid = threadIdx.x;
     x = tid % N;
     y0 = tid / N;
@@ -488,6 +582,21 @@ struct PlaneWG {
     qe = min(fa.P, qb + fa.chunk);
     zo = unsigned(z * N * N + y0 * N + x);
     so0 = y0 * F::LD + x;
+    sx = F::COMB ? sigma48(x) : x;
+  }
+  // LDS offset of owned point i in natural order (inputs of a transform; outputs of one whose input was
+  // in sigma order)
+  __device__ __forceinline__ int so(int i) const { return so0 + F::RB * F::LD * i; }
+  // LDS offset of owned point i after a transform of natural-order input (sigma order at N = 48)
+  __device__ __forceinline__ int ss(int i) const {
+    if constexpr (F::COMB)
+      return sigma48(y0 + F::RB * i) * F::LD + sx;
+    else
+      return so(i);
+  }
+  // between a round's reads at ss() and the next round's writes at so(): a barrier where they differ
+  __device__ __forceinline__ void end_round() const {
+    if constexpr (F::COMB) __syncthreads();
   }
 };
 
@@ -520,8 +629,9 @@ __global__ void __launch_bounds__((Fz<R, N>::NTH)) k_pair_xy(const cx<R>* bra, c
     for (int cc = 0; cc < nq; ++cc) {
       cx<R>* dst = out + (long(wg.t) * fa.P + q0 + cc) * NR + wg.zo;
 #pragma unroll
-      for (int i = 0; i < KP; ++i) dst[RB * N * i] = sm[cc * F::PLANE + wg.so0 + RB * F::LD * i];
+      for (int i = 0; i < KP; ++i) dst[RB * N * i] = sm[cc * F::PLANE + wg.ss(i)];
     }
+    wg.end_round();
   }
 }
 
@@ -529,12 +639,12 @@ __global__ void __launch_bounds__((Fz<R, N>::NTH)) k_pair_xy(const cx<R>* bra, c
 // m3b5 conj(Hl_qd) psi_t, with Zl = B (m2bx2 D_j - m3b3 h1 psi_j + m3b4 h4_j) and Hl = B conj(H3b)
 // (TC mode: chi = psi and H3b = conj(H3a4), so Hl = B H3a4); forward xy transformed:
 // out[(pair 2 + 0)] = kappa_1 T~_1 + kappa_2 T~_2, out[(pair 2 + 1)] = T~_3, pair = t P + q, Delta = k_t - k_q.
-// FP32 at 24^3: no register prefetch of the partner fields, 4 waves per SIMD instead (no spills); elsewhere
-// the prefetch
+// FP32 at 24^3: no register prefetch of the partner fields, 4 waves per SIMD instead (no spills); at 48
+// points none either (768-thread work-groups); elsewhere the prefetch
 template <typename R, int N>
-constexpr bool kPassBPrefetch = !(sizeof(R) == 4 && N == 24);
+constexpr bool kPassBPrefetch = !(sizeof(R) == 4 && N == 24) && Fz<R, N>::PREFETCH;
 template <typename R, int N>
-constexpr int kPassBWaves = kPassBPrefetch<R, N> ? 1 : 4;
+constexpr int kPassBWaves = (sizeof(R) == 4 && N == 24) ? 4 : 1;
 
 template <typename R, int N>
 __global__ void __launch_bounds__((Fz<R, N>::NTH)) __attribute__((amdgpu_waves_per_eu(kPassBWaves<R, N>)))
@@ -605,13 +715,14 @@ k_passB_xy(const cx<R>* psi, const cx<R>* chi, const cx<R>* Zl, const cx<R>* Hl,
       cx<R>* dst = out + (long(wg.t) * fa.P + q) * 2 * NR;
 #pragma unroll
       for (int i = 0; i < KP; ++i) {
-        const int so = (3 * a) * F::PLANE + wg.so0 + RB * F::LD * i;
+        const int so = (3 * a) * F::PLANE + wg.ss(i);
         const unsigned r = wg.zo + RB * N * i;
         const R k2 = R(double(mfreq<N>(wg.y0 + RB * i)) + del[1]);
         dst[r] = k1 * sm[so] + k2 * sm[so + F::PLANE];
         dst[NR + r] = sm[so + 2 * F::PLANE];
       }
     }
+    wg.end_round();
   }
 }
 
@@ -714,6 +825,156 @@ k_zconv(const cx<R>* in, cx<R>* out, long npairs, int t0, MeshInfo mi, Tables tb
     cx<R>* o = out + pair * NR + xy;
 #pragma unroll
     for (int z = 0; z < N; ++z) o[z * NN] = acc[z];
+  }
+}
+
+// ---------------------------------------------------------------- 48-point z stage on lane pairs
+// A 48-point column split over two adjacent lanes (h = lane & 1): radix 2 by decimation in frequency, then
+// the 24-point prime-factor transform in registers.  Lane h holds z = 24 h + j (j < 24) in real space and
+// frequency k = 2 j + h after the forward half.  The butterfly partner of each value is in lane ^ 1,
+// read with a DPP quad permutation (no LDS, no barrier).  One thread then holds 24 values per field
+// instead of 48, which keeps the z stage at 3 waves per SIMD.
+template <typename R>
+__device__ __forceinline__ R lane_swap(R v) {   // the value of lane ^ 1
+  if constexpr (sizeof(R) == 4) {
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, false));
+  } else {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_mov_dpp(int(b), 0xB1, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp(int(b >> 32), 0xB1, 0xF, 0xF, false);
+    return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned>(lo));
+  }
+}
+template <typename R>
+__device__ __forceinline__ cx<R> lane_swap(cx<R> v) { return mk<R>(lane_swap(v.x), lane_swap(v.y)); }
+
+// r e^{DIR 2 pi i j / 48} on lanes h = 1 (hf = 1), r on lanes h = 0 (hf = 0): r + hf (r w - r), with the
+// twiddle w read from the constant table (uniform), so that no per-lane twiddle is kept in registers
+template <typename R, int DIR>
+__device__ __forceinline__ cx<R> half_twiddle_mul(cx<R> r, int j, R hf) {
+  const cx<R> w = twiddle<R, 48, DIR>(j);
+  const cx<R> d = mk<R>(r.x * w.x - r.y * w.y - r.x, r.x * w.y + r.y * w.x - r.y);
+  return mk<R>(r.x + hf * d.x, r.y + hf * d.y);
+}
+
+// forward: x[24 h + j] -> X[2 j + h]; hf = h (0 or 1)
+template <typename R>
+__device__ __forceinline__ void fwd48_pair(cx<R>* v, R hf) {
+  const R s = R(1) - R(2) * hf;
+#pragma unroll
+  for (int j = 0; j < 24; ++j) {
+    const cx<R> o = lane_swap(v[j]);
+    const cx<R> r = mk<R>(o.x + s * v[j].x, o.y + s * v[j].y);   // h = 0: x_j + x_j+24; h = 1: x_j - x_j+24
+    v[j] = j == 0 ? r : half_twiddle_mul<R, -1>(r, j, hf);
+  }
+  fft_line<R, 24, -1>(v);
+}
+
+// inverse (unnormalised): X[2 j + h] -> x[24 h + j]
+template <typename R>
+__device__ __forceinline__ void inv48_pair(cx<R>* v, R hf) {
+  fft_line<R, 24, 1>(v);   // h = 0: even-frequency part e_j; h = 1: odd part o_j
+  const R s = R(1) - R(2) * hf;
+#pragma unroll
+  for (int j = 0; j < 24; ++j) {
+    const cx<R> t = j == 0 ? v[j] : half_twiddle_mul<R, 1>(v[j], j, hf);   // h = 1: e^{2 pi i j/48} o_j
+    const cx<R> o = lane_swap(t);
+    v[j] = mk<R>(o.x + s * t.x, o.y + s * t.y);   // h = 0: e_j + w o_j; h = 1: e_j - w o_j
+  }
+}
+
+// The z stage of k_zconv at N = 48 with each column on a lane pair (same operations, inputs and outputs).
+template <typename R, int OP>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 3 : 2)))
+k_zconv48(const cx<R>* in, cx<R>* out, long npairs, int t0, MeshInfo mi, Tables tb, int sign_target_minus_partner,
+          const cx<R>* inB = nullptr) {
+  constexpr int N = 48, H = 24, NN = N * N;
+  constexpr long NR = long(N) * N * N;
+  constexpr int NIN = OpShape<OP>::nin, NOUT = OpShape<OP>::nout;
+  const long gid = long(blockIdx.x) * blockDim.x + threadIdx.x;
+  const long col = gid >> 1;
+  const bool h = (threadIdx.x & 1) != 0;
+  const R hf = h ? R(1) : R(0);
+  // both lanes of a pair run every instruction (the grid covers whole pairs: npairs * NN * 2 threads)
+  if (col >= npairs * NN) return;
+  const long pair = col / NN;
+  const int xy = int(col - pair * NN);
+  const int t = int(pair / mi.P), q = int(pair - long(t) * mi.P);
+  const int di = pair_dindex(mi, t0 + t, q, sign_target_minus_partner);
+  // frequency of element j after the forward half: k = 2 j + h; real-space z = 24 h + j
+  const long kof = long(di) * NR + xy + (h ? NN : 0);
+  const R* tV = reinterpret_cast<const R*>(tb.V) + kof;
+  const R* tU0 = reinterpret_cast<const R*>(tb.U1) + kof;
+  const R* tU1 = reinterpret_cast<const R*>(tb.U2) + kof;
+  // kappa_3 = m_z + delta_3 at frequency 2 j + h: m(2 j) + h + delta_3 (2 j and 2 j + 1 never straddle N/2)
+  const R d3h = R(tb.dfr[3 * di + 2]) + hf;
+  const int zo = h ? H * NN : 0;
+  auto kap3 = [&](int j) { return R(mfreq<N>(2 * j)) + d3h; };
+
+  if constexpr (NIN == 1) {
+    cx<R> acc[H], v[H];
+    const cx<R>* b = in + pair * NR + xy + zo;
+#pragma unroll
+    for (int j = 0; j < H; ++j) acc[j] = b[j * NN];
+    fwd48_pair(acc, hf);
+    __builtin_amdgcn_sched_barrier(0);   // phases in order: one field's values in registers at a time
+    cx<R>* o = out + pair * NOUT * NR + xy + zo;
+    if constexpr (OP == OP_A1) {
+#pragma unroll
+      for (int j = 0; j < H; ++j) v[j] = tV[2 * j * NN] * acc[j];
+      inv48_pair(v, hf);
+#pragma unroll
+      for (int j = 0; j < H; ++j) o[j * NN] = v[j];
+      __builtin_amdgcn_sched_barrier(0);
+      o += NR;
+    }
+#pragma unroll 1
+    for (int s = 0; s < 2; ++s) {
+      const R* tu = s ? tU1 : tU0;
+#pragma unroll
+      for (int j = 0; j < H; ++j) v[j] = tu[2 * j * NN] * acc[j];
+      inv48_pair(v, hf);
+#pragma unroll
+      for (int j = 0; j < H; ++j) o[j * NN] = v[j];
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int j = 0; j < H; ++j) v[j] = mul_i((kap3(j) * tu[2 * j * NN]) * acc[j]);
+      inv48_pair(v, hf);
+#pragma unroll
+      for (int j = 0; j < H; ++j) o[NR + j * NN] = v[j];
+      __builtin_amdgcn_sched_barrier(0);
+      o += 2 * NR;
+    }
+  } else {
+    cx<R> acc[H], v[H];
+#pragma unroll
+    for (int j = 0; j < H; ++j) acc[j] = mk<R>(R(0), R(0));
+    const int nch = NIN / 2 + ((OP == OP_A2 && inB) ? 1 : 0);
+#pragma unroll 1
+    for (int s = 0; s < nch; ++s) {
+      const bool isB = s == NIN / 2;
+      const cx<R>* b = (isB ? inB + pair * 2 * NR : in + (pair * NIN + 2 * s) * NR) + xy + zo;
+      const R* tu = (s == 1 && !isB) ? tU1 : tU0;
+      const R sg = isB ? R(-1) : R(1);
+#pragma unroll
+      for (int j = 0; j < H; ++j) v[j] = b[j * NN];
+      fwd48_pair(v, hf);
+#pragma unroll
+      for (int j = 0; j < H; ++j) acc[j] = acc[j] + (sg * tu[2 * j * NN]) * v[j];
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int j = 0; j < H; ++j) v[j] = b[NR + j * NN];
+      fwd48_pair(v, hf);
+#pragma unroll
+      for (int j = 0; j < H; ++j) acc[j] = acc[j] + (kap3(j) * (sg * tu[2 * j * NN])) * v[j];
+      __builtin_amdgcn_sched_barrier(0);
+    }
+#pragma unroll
+    for (int j = 0; j < H; ++j) acc[j] = OP == OP_A2 ? mul_i(R(-1) * acc[j]) : mul_i(acc[j]);
+    inv48_pair(acc, hf);
+    cx<R>* o = out + pair * NR + xy + zo;
+#pragma unroll
+    for (int j = 0; j < H; ++j) o[j * NN] = acc[j];
   }
 }
 
@@ -976,6 +1237,7 @@ k_fused_A(const cx<R>* buf5, const cx<R>* psi, const cx<R>* Dl, const cx<R>* Hl,
   using F = Fz<R, N>;
   constexpr int KP = F::KP, RB = F::RB, PL = F::PLANE;
   constexpr bool SPLIT = PassA<R, N>::SPLIT;
+  constexpr bool PF = !SPLIT && F::PREFETCH;
   constexpr long NR = long(N) * N * N;
   __shared__ cx<R> sm[PassA<R, N>::NPL * PL];
   const PlaneWG<R, N> wg(fa);
@@ -1003,7 +1265,7 @@ k_fused_A(const cx<R>* buf5, const cx<R>* psi, const cx<R>* Dl, const cx<R>* Hl,
 #pragma unroll
       for (int i = 0; i < KP; ++i) pre[f][i] = ldo(src + f * NR, ob[i]);
   };
-  if (!SPLIT && wg.qb < wg.qe) fetch(wg.qb);
+  if (PF && wg.qb < wg.qe) fetch(wg.qb);
   for (int q = wg.qb; q < wg.qe; ++q) {
     const R wq = R(w[q]);
     const long pair = long(wg.t) * fa.P + q;
@@ -1024,26 +1286,26 @@ k_fused_A(const cx<R>* buf5, const cx<R>* psi, const cx<R>* Dl, const cx<R>* Hl,
         const unsigned o = wg.zo + RB * N * i;
         const R k2 = R(double(mfreq<N>(wg.y0 + RB * i)) + del[1]);
         if (par) {
-          sm[so] = SPLIT ? src[o] : pre[0][i];
-          const cx<R> w0 = SPLIT ? src[NR + o] : pre[1][i];
+          sm[so] = !PF ? src[o] : pre[0][i];
+          const cx<R> w0 = !PF ? src[NR + o] : pre[1][i];
           sm[PL + so] = mul_i(k1 * w0);
           sm[2 * PL + so] = mul_i(k2 * w0);
-          sm[3 * PL + so] = SPLIT ? src[2 * NR + o] : pre[2][i];
+          sm[3 * PL + so] = !PF ? src[2 * NR + o] : pre[2][i];
         }
         if (anti) {
-          const cx<R> w0 = SPLIT ? src[3 * NR + o] : pre[3][i];
+          const cx<R> w0 = !PF ? src[3 * NR + o] : pre[3][i];
           sm[ab * PL + so] = mul_i(k1 * w0);
           sm[(ab + 1) * PL + so] = mul_i(k2 * w0);
-          sm[(ab + 2) * PL + so] = SPLIT ? src[4 * NR + o] : pre[4][i];
+          sm[(ab + 2) * PL + so] = !PF ? src[4 * NR + o] : pre[4][i];
         }
       }
-      if (!SPLIT && q + 1 < wg.qe) fetch(q + 1);
+      if (PF && q + 1 < wg.qe) fetch(q + 1);
       __syncthreads();
       planes_fft<R, N, 1>(sm, SPLIT ? (g == 0 ? 4 : 3) : 7, threadIdx.x);
 #pragma unroll
       for (int i = 0; i < KP; ++i) {
         const unsigned r = wg.zo + RB * N * i;
-        const int so = wg.so0 + RB * F::LD * i;
+        const int so = wg.ss(i);
         if (par) {
           const cx<R> p = ldo(pq, ob[i]);
           cfma(ga[i][0], a0 * wq, sm[so], p);
@@ -1149,10 +1411,11 @@ __global__ void __launch_bounds__((Fz<R, N>::NTH)) k_fused_Y(const cx<R>* buf1, 
 #pragma unroll
     for (int i = 0; i < KP; ++i) {
       const long r = wg.zo + RB * N * i;
-      const int so = wg.so0 + RB * F::LD * i;
+      const int so = wg.ss(i);
       for (int cc = 0; cc < nq; ++cc)
         cfma(ga[i], R(coef * w[q0 + cc]), sm[cc * F::PLANE + so], psi[long(q0 + cc) * NR + r]);
     }
+    wg.end_round();
   }
 #pragma unroll
   for (int i = 0; i < KP; ++i) gpart[(long(wg.c) * fa.T + wg.t) * NR + wg.zo + RB * N * i] = ga[i];
@@ -1179,6 +1442,7 @@ __global__ void __launch_bounds__((Fz<R, N>::NTH)) k_fused_O(const cx<R>* buf4, 
   using F = Fz<R, N>;
   constexpr int KP = F::KP, RB = F::RB, PL = F::PLANE;
   constexpr bool SPLIT = PassO<R, N>::SPLIT;
+  constexpr bool PF = !SPLIT && F::PREFETCH;
   if (sT < 0) sT = 4L * fa.P;
   constexpr long NR = long(N) * N * N;
   __shared__ cx<R> sm[PassO<R, N>::NPL * PL];
@@ -1216,7 +1480,7 @@ __global__ void __launch_bounds__((Fz<R, N>::NTH)) k_fused_O(const cx<R>* buf4, 
 #pragma unroll
       for (int i = 0; i < KP; ++i) pre[f][i] = src[f * NR + RB * N * i];
   };
-  if (!SPLIT && wg.qb < wg.qe) fetch(wg.qb);
+  if (PF && wg.qb < wg.qe) fetch(wg.qb);
   for (int q = wg.qb; q < wg.qe; ++q) {
     const R wq = R(w[q]);
     const double* del = dfr + 3 * pair_dindex(mi, ja, q, 0);
@@ -1232,25 +1496,25 @@ __global__ void __launch_bounds__((Fz<R, N>::NTH)) k_fused_O(const cx<R>* buf4, 
         const long o = RB * N * i;
         const R k2 = R(double(mfreq<N>(wg.y0 + RB * i)) + del[1]);
         if (par) {
-          const cx<R> w0 = SPLIT ? src[o] : pre[0][i];
+          const cx<R> w0 = !PF ? src[o] : pre[0][i];
           sm[so] = mul_i(k1 * w0);
           sm[PL + so] = mul_i(k2 * w0);
-          sm[2 * PL + so] = SPLIT ? src[NR + o] : pre[1][i];
+          sm[2 * PL + so] = !PF ? src[NR + o] : pre[1][i];
         }
         if (anti) {
-          const cx<R> w0 = SPLIT ? src[2 * NR + o] : pre[2][i];
+          const cx<R> w0 = !PF ? src[2 * NR + o] : pre[2][i];
           sm[ab * PL + so] = mul_i(k1 * w0);
           sm[(ab + 1) * PL + so] = mul_i(k2 * w0);
-          sm[(ab + 2) * PL + so] = SPLIT ? src[3 * NR + o] : pre[3][i];
+          sm[(ab + 2) * PL + so] = !PF ? src[3 * NR + o] : pre[3][i];
         }
       }
-      if (!SPLIT && q + 1 < wg.qe) fetch(q + 1);
+      if (PF && q + 1 < wg.qe) fetch(q + 1);
       __syncthreads();
       planes_fft<R, N, 1>(sm, SPLIT ? 3 : 6, threadIdx.x);
 #pragma unroll
       for (int i = 0; i < KP; ++i) {
         const long r = wg.zo + RB * N * i;
-        const int so = wg.so0 + RB * F::LD * i;
+        const int so = wg.ss(i);
         cx<R> Y[3];
         if (par) {
           const cx<R> pq = psi[long(q) * NR + r];
@@ -1274,6 +1538,7 @@ __global__ void __launch_bounds__((Fz<R, N>::NTH)) k_fused_O(const cx<R>* buf4, 
             h5[i] += v;
         }
       }
+      wg.end_round();
     }
   }
 #pragma unroll
@@ -1382,7 +1647,7 @@ __global__ void __launch_bounds__((Fz<R, N>::NTH)) k_fused_OB(const cx<R>* buf21
         planes_fft<R, N, 1>(sm, SPLIT ? 3 : 6, threadIdx.x);
 #pragma unroll
         for (int i = 0; i < KP; ++i) {
-          const int so = wg.so0 + RB * F::LD * i;
+          const int so = wg.ss(i);
           cx<R> Y[3], X12[3];
           if (!SPLIT || h == 0) {
 #pragma unroll
