@@ -100,6 +100,24 @@ enum {
  * until orbitals are loaded.  TC_ERR_DEVICE if the device is unusable. */
 int tc_create(int device, void* stream, tc_ctx** out);
 
+/* Device memory of the context from the caller (the memory the problem statement leaves to PyTorch):
+ * every device buffer the library makes after this call comes from alloc_fn(bytes, user) and goes back
+ * through free_fn(p, bytes, user) (bytes as allocated).  The context's stream is drained before a
+ * buffer is given back.  Buffers made earlier keep the allocator that made them (hipMalloc before any
+ * call).  alloc_fn returning NULL is TC_ERR_OOM at the call that needed the memory.  Both NULL: hipMalloc
+ * again; one NULL: TC_ERR_ARG.  The functions and `user` must stay valid until tc_destroy. */
+int tc_set_allocator(tc_ctx* ctx, void* (*alloc_fn)(size_t bytes, void* user),
+                     void (*free_fn)(void* p, size_t bytes, void* user), void* user);
+
+/* Bytes of device memory the resident pair store and the per-batch pair buffers (the two large
+ * consumers) may take together; 0 (the default) sizes them from the device's memory.  With a budget the
+ * store is kept when it and a batch of 8 targets fit, and the batches take what it leaves (at most
+ * 32 GiB).  The next application resizes.  Results do not depend on it. */
+int tc_set_memory_budget(tc_ctx* ctx, size_t bytes);
+
+/* The hipStream_t the context enqueues its work on (the caller's, or the one it created). */
+void* tc_get_stream(const tc_ctx* ctx);
+
 /* Release every device buffer and the owned stream.  NULL is ignored. */
 void tc_destroy(tc_ctx* ctx);
 
@@ -234,6 +252,7 @@ int tc_apply_all(tc_ctx* ctx, double* out);
 /* Same, writing to a caller-owned device buffer of the same layout (may be NULL:
  * the result then stays inside the context).  Asynchronous on the stream. */
 int tc_apply_all_dev(tc_ctx* ctx, void* out_dev);
+
 
 /* Pseudo-energy per cell (reading of Eqs. EtotTC / EtotBiTC: (1/N_k) Re sum_{sigma,k,mu}
  * f <chi| T + h2/2 + h3/3 |phi>, chi = phi in TC mode) of the last application (runs

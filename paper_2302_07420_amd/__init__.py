@@ -40,6 +40,9 @@ KERNELS = ("k_scatter", "k_fft_xy<R,N,-1>", "k_fft_xy<R,N,1>", "k_fft_z<R,N,-1>"
 STAGES = ("g_to_r", "hartree", "occ_occ", "pass_a", "pass_b", "out_and_corrections")
 
 _lib = None
+# tc_set_allocator callbacks: void* alloc(size_t bytes, void* user); void free(void* p, size_t bytes, void* user)
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
 
 
 class TCError(RuntimeError):
@@ -98,6 +101,9 @@ def lib():
         "tc_set_pair_store": (I, [P, I]),
         "tc_set_profiling": (I, [P, I]),
         "tc_kernel_stats": (I, [P, dp, dp, dp, I]),
+        "tc_set_allocator": (I, [P, ALLOC_FN, FREE_FN, P]),
+        "tc_set_memory_budget": (I, [P, ctypes.c_size_t]),
+        "tc_get_stream": (P, [P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -134,6 +140,34 @@ class TCOperator:
         if getattr(self, "_h", None):
             self._L.tc_destroy(self._h)
             self._h = None
+        self._alloc_cb = None   # the allocator callbacks outlive the context
+
+    def stream(self) -> int:
+        """The hipStream_t (as an integer) the library enqueues this context's work on."""
+        return int(self._L.tc_get_stream(self._h) or 0)
+
+    def use_torch_allocator(self, device: int = 0):
+        """Take every later device buffer of the context from PyTorch's caching allocator (on the context's
+        stream), so that torch.cuda.memory_allocated() counts it; tc_destroy gives it back."""
+        import torch
+
+        stream = self.stream()
+
+        def _alloc(nbytes, user):
+            try:
+                return torch.cuda.caching_allocator_alloc(int(nbytes), device, stream)
+            except Exception:   # out of memory: the library reports TC_ERR_OOM
+                return None
+
+        def _free(ptr, nbytes, user):
+            torch.cuda.caching_allocator_delete(ptr)
+
+        cbs = (ALLOC_FN(_alloc), FREE_FN(_free))
+        self._check(self._L.tc_set_allocator(self._h, cbs[0], cbs[1], None), "tc_set_allocator")
+        self._alloc_cb = cbs
+
+    def set_memory_budget(self, nbytes: int):
+        self._check(self._L.tc_set_memory_budget(self._h, int(nbytes)), "tc_set_memory_budget")
 
     def __del__(self):
         try:
@@ -375,10 +409,16 @@ class TCOperator:
 
 def from_workload(w, precision=TC_PREC_FP64, terms=TERM_ALL, div_correction=True, device=0, A=None, C=None,
                   coeff=None, stream=None, batch=0, left=None, symmetry=None, pair_store=True,
-                  reading="printed") -> TCOperator:
+                  reading="printed", torch_alloc=False, mem_budget=0) -> TCOperator:
     """Build an operator from a ``tcinputs.Workload``: TC mode, or the biorthogonal mode when the workload
-    (or ``left``) holds left orbitals; ``symmetry``: crystal operations [(R, tau)] (see set_symmetry)."""
+    (or ``left``) holds left orbitals; ``symmetry``: crystal operations [(R, tau)] (see set_symmetry);
+    ``torch_alloc``: device memory from PyTorch's caching allocator; ``mem_budget``: bytes for the pair
+    store and pair buffers (tc_set_memory_budget)."""
     op = TCOperator(device, stream)
+    if torch_alloc:
+        op.use_torch_allocator(device)
+    if mem_budget:
+        op.set_memory_budget(mem_budget)
     if batch:
         op.set_batch(batch)
     if not pair_store:

@@ -16,7 +16,10 @@
 #include <complex>
 #include <cstdio>
 #include <cstring>
+#include <functional>
+#include <list>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <thread>
 #include <type_traits>
@@ -172,6 +175,7 @@ struct Problem {
   std::vector<char> loaded_dn;            // per k (nspin = 2)
   double delta_gb = 0, sigma_aux = 0;
   int batch = 0;                          // targets per batch (0 = automatic)
+  size_t mem_budget = 0;                  // bytes for the pair store and pair buffers (0: from the device)
   int pair_store = 1;                     // keep every pair's pass-A z-stage output resident when it fits
   // crystal symmetry (tc_set_symmetry): operations x -> R (x + tau) and the k-point orbits
   int nsym = 0;
@@ -237,25 +241,96 @@ void gb_constant(Problem& pb) {
 }
 
 // ------------------------------------------------------------------ device buffers
+// Where device memory comes from during a C-ABI call (thread-local, set by the entry point for its context):
+//   t_alloc: the caller's allocator (tc_set_allocator), else hipMalloc / hipFree;
+//   t_arena: the scratch of the no-allocation entry point: every allocation of the call is carved from it
+//            and every release is deferred, and both are undone when the call ends (ArenaScope).
+struct DevAlloc {
+  void* (*alloc)(size_t bytes, void* user) = nullptr;
+  void (*free)(void* p, size_t bytes, void* user) = nullptr;
+  void* user = nullptr;
+  hipStream_t stream = nullptr;   // the context's stream: drained before memory goes back to the caller
+};
+struct Arena;
+thread_local const DevAlloc* t_alloc = nullptr;
+thread_local Arena* t_arena = nullptr;
+
+struct Arena {
+  char* base = nullptr;
+  size_t cap = 0, used = 0;
+  std::vector<std::function<void()>> undo;   // restores the buffers rebound during the call, newest first
+  char* carve(size_t bytes) {
+    const size_t off = (used + 255) & ~size_t(255);
+    if (off + bytes > cap)
+      throw TcError(TC_ERR_OOM, "the no-allocation scratch holds " + std::to_string(cap) + " bytes; this call needs more than " +
+                                    std::to_string(off + bytes) + " (fewer targets per batch, tc_set_batch, may fit)");
+    used = off + bytes;
+    return base + off;
+  }
+};
+
 template <typename T>
 struct DBuf {
   T* p = nullptr;
   size_t n = 0;
+  const DevAlloc* al = nullptr;   // the allocator that made p (null: hipMalloc)
+  bool carved = false;            // p lies in the no-allocation scratch
+  void remember() {               // under an arena: the state to restore when the call ends
+    t_arena->undo.push_back([this, p0 = p, n0 = n, al0 = al, c0 = carved] {
+      p = p0;
+      n = n0;
+      al = al0;
+      carved = c0;
+    });
+  }
   void alloc(size_t count) {
+    if (t_arena) {   // rebind to the scratch (a buffer carved earlier in this call is reused when large enough)
+      if (carved && count <= n) return;
+      remember();
+      p = count ? reinterpret_cast<T*>(t_arena->carve(count * sizeof(T))) : nullptr;
+      n = count;
+      al = nullptr;
+      carved = true;
+      return;
+    }
     if (count <= n && p) return;
     release();
     if (count == 0) return;
-    hipError_t e = hipMalloc(&p, count * sizeof(T));
-    if (e != hipSuccess) {
-      p = nullptr;
-      throw TcError(TC_ERR_OOM, "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed");
+    if (t_alloc && t_alloc->alloc) {
+      p = static_cast<T*>(t_alloc->alloc(count * sizeof(T), t_alloc->user));
+      if (!p) throw TcError(TC_ERR_OOM, "the caller's allocator returned NULL for " + std::to_string(count * sizeof(T)) + " bytes");
+      al = t_alloc;
+    } else {
+      hipError_t e = hipMalloc(&p, count * sizeof(T));
+      if (e != hipSuccess) {
+        p = nullptr;
+        throw TcError(TC_ERR_OOM, "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed");
+      }
+      al = nullptr;
     }
     n = count;
   }
   void release() {
-    if (p) (void)hipFree(p);
+    if (t_arena) {   // no free inside the no-allocation call: hide the buffer until the call ends
+      if (!p) return;
+      if (!carved) remember();
+      p = nullptr;
+      n = 0;
+      carved = false;
+      return;
+    }
+    if (p && !carved) {
+      if (al) {
+        (void)hipStreamSynchronize(al->stream);   // no queued kernel may still use the memory
+        al->free(p, n * sizeof(T), al->user);
+      } else {
+        (void)hipFree(p);
+      }
+    }
     p = nullptr;
     n = 0;
+    al = nullptr;
+    carved = false;
   }
   ~DBuf() { release(); }
 };
@@ -828,16 +903,28 @@ inline bool need_corr(const Problem& pb, const Masks& m) {
   return pb.div && (pb.mask & TC_T_CORR) && (m.m2ax || m.m3a2 || m.m3b6 || rem_2bx1(pb));
 }
 
+// Stage-timing events of one application.  The no-allocation entry point creates none (its stage times
+// read 0): rec() and ms() then do nothing and sync() waits on the stream.
 struct Events {
   std::vector<hipEvent_t> e;
-  explicit Events(int n) : e(n, nullptr) {
+  explicit Events(int n) : e(t_arena ? 0 : n, nullptr) {
     for (auto& x : e) TC_HIP(hipEventCreate(&x));
   }
   ~Events() {
     for (auto& x : e)
       if (x) (void)hipEventDestroy(x);
   }
+  void rec(int i, hipStream_t s) {
+    if (i < int(e.size())) TC_HIP(hipEventRecord(e[i], s));
+  }
+  void sync(int i, hipStream_t s) {
+    if (i < int(e.size()))
+      TC_HIP(hipEventSynchronize(e[i]));
+    else
+      TC_HIP(hipStreamSynchronize(s));
+  }
   float ms(int a, int b) const {
+    if (e.empty()) return 0.f;
     float t = 0;
     TC_HIP(hipEventElapsedTime(&t, e[a], e[b]));
     return t;
@@ -1108,20 +1195,34 @@ struct EngineT : Engine {
 
   void release_pair_store() override { allB.release(); }
 
-  // The resident store of pass-A z-stage outputs: allocated when it leaves a quarter of the device (at
-  // least 16 GiB) free, released when it does not fit.
+  // Bytes of per-batch pair buffers (bufA, bufB) of one target, and of the smallest batch worth keeping
+  // next to the resident store
+  static size_t per_target_bytes(const Problem& pb) {
+    return size_t(pb.P()) * ((pb.bitc ? 8 : 5) + 4) * NR * sizeof(cx<R>);
+  }
+
+  // The resident store of pass-A z-stage outputs.  Without a caller budget: allocated when it leaves a
+  // quarter of the device (at least 16 GiB) free.  With one (tc_set_memory_budget): when the store and
+  // a batch of 8 targets fit in it.  Released when it does not fit; never under the no-allocation scratch.
   bool pair_store(const Problem& pb) {
     const size_t need = size_t(5) * pb.P() * pb.P() * NR;
+    if (t_arena) return false;
     if (!pb.pair_store) {
+      allB.release();
+      return false;
+    }
+    const size_t bytes = need * sizeof(cx<R>);
+    if (pb.mem_budget && bytes + per_target_bytes(pb) * std::min(8, pb.P()) > pb.mem_budget) {
       allB.release();
       return false;
     }
     if (allB.n >= need) return true;
     allB.release();
-    size_t fr = 0, tot = 0;
-    if (hipMemGetInfo(&fr, &tot) != hipSuccess) return false;
-    const size_t bytes = need * sizeof(cx<R>);
-    if (bytes + std::max<size_t>(tot / 4, size_t(16) << 30) > fr) return false;
+    if (!pb.mem_budget) {
+      size_t fr = 0, tot = 0;
+      if (hipMemGetInfo(&fr, &tot) != hipSuccess) return false;
+      if (bytes + std::max<size_t>(tot / 4, size_t(16) << 30) > fr) return false;
+    }
     try {
       allB.alloc(need);
     } catch (const TcError&) {
@@ -1130,11 +1231,17 @@ struct EngineT : Engine {
     return true;
   }
 
-  // Bytes of per-batch pair buffers: an eighth of the device's memory, between 8 and 32 GiB (32 GiB on a
-  // 288 GB device: 134 targets per batch at 256 orbitals and 24^3 in FP32).  Larger batches mean fewer,
-  // larger launches and fewer partial tails.
+  // Bytes of per-batch pair buffers.  Without a caller budget: an eighth of the device's memory, between
+  // 8 and 32 GiB (32 GiB on a 288 GB device: 134 targets per batch at 256 orbitals and 24^3 in FP32);
+  // larger batches mean fewer, larger launches and fewer partial tails.  With a budget: what the store
+  // leaves of it, at most 32 GiB.  Under the no-allocation scratch: a third of what is left of it.
   size_t budget_ = 0;
-  size_t pair_budget() {
+  size_t pair_budget(const Problem& pb) {
+    if (t_arena) return (t_arena->cap - t_arena->used) / 3;
+    if (pb.mem_budget) {
+      const size_t store = allB.p ? allB.n * sizeof(cx<R>) : 0;
+      return std::min(size_t(32) << 30, pb.mem_budget > store ? pb.mem_budget - store : size_t(0));
+    }
     if (!budget_) {
       size_t fr = 0, tot = 0;
       if (hipMemGetInfo(&fr, &tot) != hipSuccess) tot = 0;
@@ -1143,9 +1250,17 @@ struct EngineT : Engine {
     return budget_;
   }
 
+  size_t budget_alloc = size_t(-1);
   void ensure(const Problem& pb, size_t budget_bytes) {
     const int P = pb.P();
-    if (P == P_alloc && pb.batch == batch_alloc && pb.bitc == bitc_alloc && pb.nspin == nspin_alloc) return;
+    // under the no-allocation scratch every buffer is bound to it again
+    if (!t_arena && P == P_alloc && pb.batch == batch_alloc && pb.bitc == bitc_alloc && pb.nspin == nspin_alloc &&
+        budget_bytes == budget_alloc)
+      return;
+    if (t_arena) t_arena->undo.push_back([this, T0 = T, S0 = S] {   // the batch shape of the ordinary buffers
+      T = T0;
+      S = S0;
+    });
     psi.alloc(size_t(P) * NR);
     D.alloc(size_t(3) * P * NR);
     Dl.alloc(size_t(3) * P * NR);
@@ -1158,7 +1273,7 @@ struct EngineT : Engine {
     // per target: 4 pair fields in bufA and 5 in bufB (8 in biorthogonal mode: V21 and V12 of the
     // occupied-occupied pass)
     const int nB = pb.bitc ? 8 : 5;
-    const size_t per_t = size_t(P) * (4 + nB) * NR * sizeof(cx<R>);
+    const size_t per_t = per_target_bytes(pb);
     T = int(std::max<size_t>(1, std::min<size_t>(size_t(P), budget_bytes / per_t)));
     if (pb.batch > 0) T = std::min(pb.batch, P);
     bufA.alloc(size_t(T) * P * 4 * NR);
@@ -1202,10 +1317,12 @@ struct EngineT : Engine {
       psi64_1.alloc(size_t(P) * NR);
       v64p.alloc(10 * NR);
     }
+    if (t_arena) return;   // the buffers of the no-allocation call are unbound when it ends
     P_alloc = P;
     batch_alloc = pb.batch;
     bitc_alloc = pb.bitc;
     nspin_alloc = pb.nspin;
+    budget_alloc = budget_bytes;
   }
 
   void apply(hipStream_t s, Shared& sh, const Problem& pb, double* stage_ms, const TargetSet* ts) override {
@@ -1222,7 +1339,16 @@ struct EngineT : Engine {
       m.m2bx1 = -m.m2bx1;
       m.m2bx2 = -m.m2bx2;
     }
-    ensure(pb, pair_budget());
+    const bool need_occ = m.m3a2 || m.m3a4 || m.m3b2 || m.m3b5;
+    const bool need_A = m.m2ax || m.m2bx1 || m.m2bx2 || m.m3a3 || m.m3a4 || m.m3b4 || m.m3b6;
+    const bool need_B = m.m2bx2 || m.m3b3 || m.m3b4 || m.m3b5;
+    // With the orbitals as targets, the pass-A pair (t = b, q = a) has the density conj(psi_a) psi_b and the
+    // momentum Delta = k_b - k_a of the occupied pair (a, b), and the four fields of its z stage after V are
+    // the occupied pass's.  When every pair's pass-A z-stage output fits on the device it is computed once,
+    // before the occupied pass, which then reads it in place of its own pair densities and z stage.  (The
+    // store is settled before the batch buffers, which take what it leaves of a caller's budget.)
+    const bool keepA = !pb.bitc && !ts && need_occ && need_A && pair_store(pb);
+    ensure(pb, pair_budget(pb));
     // targets: the orbitals, or nbt trial vectors per k-point
     const int nbt = ts ? ts->nvec : nb;
     const int NTG = (ts && ts->nblk ? ts->nblk : pb.nk) * nbt;
@@ -1256,7 +1382,7 @@ struct EngineT : Engine {
     };
     Events ev(6);
     std::vector<hipEvent_t> bev;   // per batch: begin A, end A, end B
-    TC_HIP(hipEventRecord(ev.e[0], s));
+    ev.rec(0, s);
 
     // ---- 0: G -> r (psi and the three components of D)
     TC_HIP(hipMemsetAsync(psi.p, 0, size_t(P) * NR * sizeof(cx<R>), s));
@@ -1298,7 +1424,7 @@ struct EngineT : Engine {
       hipLaunchKernelGGL((k_lattice3<R, N>), dim3(nblk(long(P) * NR)), dim3(256), 0, s, D.p, Dl.p, bm, long(P), NR,
                          long(P) * NR);
     });
-    TC_HIP(hipEventRecord(ev.e[1], s));
+    ev.rec(1, s);
 
     // ---- 1: densities and Hartree-type fields (Algs. 2ah, 3a1, 3b1; 2bh1, 2bh2)
     TC_HIP(hipMemsetAsync(loc.p, 0, 8 * NR * sizeof(cx<R>), s));
@@ -1323,18 +1449,10 @@ struct EngineT : Engine {
     });
     fft3d_t<R, N>(wk.p + 3 * NR, 1, +1, s, pf);
     TC_HIP(hipMemcpyAsync(loc.p + 5 * NR, wk.p + 3 * NR, NR * sizeof(cx<R>), hipMemcpyDeviceToDevice, s));
-    TC_HIP(hipEventRecord(ev.e[2], s));
+    ev.rec(2, s);
 
     // ---- 2: occupied-occupied pair pass (Algs. 3a2, 3a4 and 3b2/3b5 first loops)
-    const bool need_occ = m.m3a2 || m.m3a4 || m.m3b2 || m.m3b5;
-    const bool need_A = m.m2ax || m.m2bx1 || m.m2bx2 || m.m3a3 || m.m3a4 || m.m3b4 || m.m3b6;
-    const bool need_B = m.m2bx2 || m.m3b3 || m.m3b4 || m.m3b5;
     const int chunk = (P + S - 1) / S;
-    // With the orbitals as targets, the pass-A pair (t = b, q = a) has the density conj(psi_a) psi_b and the
-    // momentum Delta = k_b - k_a of the occupied pair (a, b), and the four fields of its z stage after V are
-    // the occupied pass's.  When every pair's pass-A z-stage output fits on the device it is computed once,
-    // before the occupied pass, which then reads it in place of its own pair densities and z stage.
-    const bool keepA = !bitc && !ts && need_occ && need_A && pair_store(pb);
     if (keepA) {
       for (int t0 = 0; t0 < P; t0 += T) {
         const int nt = std::min(T, P - t0);
@@ -1430,7 +1548,7 @@ struct EngineT : Engine {
         hipLaunchKernelGGL((k_lattice3<R, N>), dim3(nblk(long(P) * NR)), dim3(256), 0, s, H3bc.p, H3bc.p, bm,
                            long(P), 3 * NR, NR);
     });
-    TC_HIP(hipEventRecord(ev.e[3], s));
+    ev.rec(3, s);
 
     // band divergence corrections: h3 of the band orbitals as rows of the occupied-occupied pass
     // (partners: the mesh orbitals; Delta = k_q - k_b), needed by the band forms of 3a4 and 3b5
@@ -1457,13 +1575,14 @@ struct EngineT : Engine {
       const long npair = long(nt) * P;
       TC_HIP(hipMemsetAsync(acc.p, 0, size_t(kAccSlots) * T * NR * sizeof(cx<double>), s));
       TC_HIP(hipMemsetAsync(h4.p, 0, size_t(3) * T * NR * sizeof(cx<R>), s));
-      for (int i = 0; i < 3; ++i) {
-        hipEvent_t e;
-        TC_HIP(hipEventCreate(&e));
-        bev.push_back(e);
-      }
-      hipEvent_t* be = &bev[bev.size() - 3];
-      TC_HIP(hipEventRecord(be[0], s));
+      if (!t_arena)
+        for (int i = 0; i < 3; ++i) {
+          hipEvent_t e;
+          TC_HIP(hipEventCreate(&e));
+          bev.push_back(e);
+        }
+      hipEvent_t* be = t_arena ? nullptr : &bev[bev.size() - 3];
+      if (be) TC_HIP(hipEventRecord(be[0], s));
       const double part = fb * nt * S;   // one working-precision field per (chunk, target)
       if (need_A) {
         const FusedArgs fa{P, nt, t0, S, chunk};
@@ -1511,7 +1630,7 @@ struct EngineT : Engine {
           });
         }
       }
-      TC_HIP(hipEventRecord(be[1], s));
+      if (be) TC_HIP(hipEventRecord(be[1], s));
       if (need_B) {
         // With 3b6 selected, its z stage (Alg. 3b6, sources in bufA) and pass B's (Algs. 3b3-3b5, sources in
         // bufB) both multiply by the parallel-channel u~ and end in the same partner sum: one OP_A2 z stage
@@ -1547,7 +1666,7 @@ struct EngineT : Engine {
                              nullptr, gpart.p, nullptr, nullptr, nullptr, acc.p, nullptr);
         });
       }
-      TC_HIP(hipEventRecord(be[2], s));
+      if (be) TC_HIP(hipEventRecord(be[2], s));
       K(TC_K_OTHER, fb * 16.0 * nt + 8.0 * fd * nt, [&] {
         hipLaunchKernelGGL((k_local<R, N>), dim3(nblk(long(nt) * NR)), dim3(256), 0, s, tP, tD, loc.p, h4.p, t0,
                            nt, NTG, m, acc.p, g.p);
@@ -1561,7 +1680,7 @@ struct EngineT : Engine {
       });
     }
     if (ts && ts->OBh4) band_grid(s, sh, pb, *ts, NTG, tP, tbox, tnpw, tkg, tnpm, rc);
-    TC_HIP(hipEventRecord(ev.e[4], s));
+    ev.rec(4, s);
 
     // ---- 5: kinetic energy and FP64 corrections
     K(TC_K_CORR, 0.0, [&] {
@@ -1572,8 +1691,8 @@ struct EngineT : Engine {
       }
       if (need_corr(pb, m) && !(ts && ts->band)) corrections(s, sh, pb, m, ts);
     });
-    TC_HIP(hipEventRecord(ev.e[5], s));
-    TC_HIP(hipEventSynchronize(ev.e[5]));
+    ev.rec(5, s);
+    ev.sync(5, s);
     if (pf && pf->on) pf->collect();
     double msA = 0, msB = 0;
     for (size_t i = 0; i + 2 < bev.size(); i += 3) {
@@ -1670,7 +1789,7 @@ struct EngineT : Engine {
     const int nirr = int(pb.irr.size());
     const int PI = nirr * nb;
     const Masks m = make_masks(pb.mask);
-    ensure(pb, pair_budget());
+    ensure(pb, pair_budget(pb));
     const MeshInfo mi{pb.n1, pb.n2, pb.n3, nb, P, nb, sh.irrk.p};   // rows / targets: representatives
     Recip rc;
     for (int i = 0; i < 9; ++i) rc.b[i] = pb.B[i];
@@ -1696,7 +1815,7 @@ struct EngineT : Engine {
     sh.epartI.alloc(size_t(kAccSlots) * PI);
     Events ev(6);
     double msA = 0, msB = 0;
-    TC_HIP(hipEventRecord(ev.e[0], s));
+    ev.rec(0, s);
 
     // ---- 0: G -> r of every orbital; the representatives' fields as targets
     TC_HIP(hipMemsetAsync(psi.p, 0, size_t(P) * NR * sizeof(cx<R>), s));
@@ -1722,7 +1841,7 @@ struct EngineT : Engine {
       hipLaunchKernelGGL((k_lattice3<R, N>), dim3(nblk(long(P) * NR)), dim3(256), 0, s, D.p, Dl.p, bm, long(P), NR,
                          long(P) * NR);
     });
-    TC_HIP(hipEventRecord(ev.e[1], s));
+    ev.rec(1, s);
 
     // ---- 1: densities and Hartree-type fields (every orbital)
     TC_HIP(hipMemsetAsync(loc.p, 0, 8 * NR * sizeof(cx<R>), s));
@@ -1747,7 +1866,7 @@ struct EngineT : Engine {
     });
     fft3d_t<R, N>(wk.p + 3 * NR, 1, +1, s, pf);
     TC_HIP(hipMemcpyAsync(loc.p + 5 * NR, wk.p + 3 * NR, NR * sizeof(cx<R>), hipMemcpyDeviceToDevice, s));
-    TC_HIP(hipEventRecord(ev.e[2], s));
+    ev.rec(2, s);
 
     // ---- 2: occupied-occupied pass with the representatives' orbitals as rows, then the images
     const bool need_occ = m.m3a2 || m.m3a4 || m.m3b2 || m.m3b5;
@@ -1794,7 +1913,7 @@ struct EngineT : Engine {
       hipLaunchKernelGGL((k_lattice3<R, N>), dim3(nblk(long(P) * NR)), dim3(256), 0, s, H3a4.p, Hl.p, bm, long(P),
                          3 * NR, NR);
     });
-    TC_HIP(hipEventRecord(ev.e[3], s));
+    ev.rec(3, s);
 
     // ---- 3/4: the representatives' orbitals as targets (partners: every orbital)
     const bool need_A = m.m2ax || m.m2bx1 || m.m2bx2 || m.m3a3 || m.m3a4 || m.m3b4 || m.m3b6;
@@ -1805,7 +1924,7 @@ struct EngineT : Engine {
       TC_HIP(hipMemsetAsync(acc.p, 0, size_t(kAccSlots) * T * NR * sizeof(cx<double>), s));
       TC_HIP(hipMemsetAsync(h4.p, 0, size_t(3) * T * NR * sizeof(cx<R>), s));
       Events bev(3);
-      TC_HIP(hipEventRecord(bev.e[0], s));
+      bev.rec(0, s);
       const double part = fb * nt * S;
       if (need_A) {
         const FusedArgs fa{P, nt, t0, S, chunk};
@@ -1839,7 +1958,7 @@ struct EngineT : Engine {
           });
         }
       }
-      TC_HIP(hipEventRecord(bev.e[1], s));
+      bev.rec(1, s);
       if (need_B) {
         // 3b6 and pass B share one z stage and one partner sum (as in the unreduced path)
         const bool merged = need_A && m.m3b6;
@@ -1872,7 +1991,7 @@ struct EngineT : Engine {
                              nullptr, gpart.p, nullptr, nullptr, nullptr, acc.p, nullptr);
         });
       }
-      TC_HIP(hipEventRecord(bev.e[2], s));
+      bev.rec(2, s);
       K(TC_K_OTHER, fb * 16.0 * nt + 8.0 * fd * nt, [&] {
         hipLaunchKernelGGL((k_local<R, N>), dim3(nblk(long(nt) * NR)), dim3(256), 0, s, psiT.p, DT.p, loc.p, h4.p, t0,
                            nt, PI, m, acc.p, g.p);
@@ -1884,7 +2003,7 @@ struct EngineT : Engine {
         hipLaunchKernelGGL((k_gather<R>), dim3(nblk(long(nt) * npm)), dim3(256), 0, s, g.p, sh.boxidx.p, sh.npw.p, nb,
                            npm, t0, nt, 1.0 / double(NR), sh.outI.p, NR, sh.irrk.p);
       });
-      TC_HIP(hipEventSynchronize(bev.e[2]));
+      bev.sync(2, s);
       msA += bev.ms(0, 1);
       msB += bev.ms(1, 2);
     }
@@ -1895,7 +2014,7 @@ struct EngineT : Engine {
       hipLaunchKernelGGL(k_sym_epart, dim3(nblk(long(P) * kAccSlots)), dim3(256), 0, s, sh.symk.p, nb, P, kAccSlots,
                          sh.epartI.p, sh.epart.p);
     });
-    TC_HIP(hipEventRecord(ev.e[4], s));
+    ev.rec(4, s);
 
     // ---- 5: kinetic energy and FP64 corrections (every orbital)
     K(TC_K_CORR, 0.0, [&] {
@@ -1904,8 +2023,8 @@ struct EngineT : Engine {
       TC_HIP(hipMemsetAsync(sh.ecorr.p, 0, size_t(2) * P * sizeof(double), s));
       if (need_corr(pb, m)) corrections(s, sh, pb, m, nullptr);
     });
-    TC_HIP(hipEventRecord(ev.e[5], s));
-    TC_HIP(hipEventSynchronize(ev.e[5]));
+    ev.rec(5, s);
+    ev.sync(5, s);
     if (pf && pf->on) pf->collect();
     stage_ms[0] = ev.ms(0, 1);
     stage_ms[1] = ev.ms(1, 2);
@@ -1924,7 +2043,7 @@ struct EngineT : Engine {
     const int nb = pb.nb;
     const int npm = pb.npw_max;
     const Masks m = make_masks(pb.mask);
-    ensure(pb, pair_budget());
+    ensure(pb, pair_budget(pb));
     const MeshInfo mi{pb.n1, pb.n2, pb.n3, nb, P, nb};
     Recip rc;
     for (int i = 0; i < 9; ++i) rc.b[i] = pb.B[i];
@@ -1955,7 +2074,7 @@ struct EngineT : Engine {
     const size_t cofs = size_t(2) * P * npm;   // doubles per channel in coefficient arrays
     Events ev(6);
     double msA = 0, msB = 0;
-    TC_HIP(hipEventRecord(ev.e[0], s));
+    ev.rec(0, s);
 
     // ---- 0: G -> r for both channels
     const unsigned gsc = nblk(long(P) * npm);
@@ -1977,7 +2096,7 @@ struct EngineT : Engine {
                            NR, long(P) * NR);
       });
     }
-    TC_HIP(hipEventRecord(ev.e[1], s));
+    ev.rec(1, s);
 
     // ---- 1: densities of both channels; Hartree-type fields of each target spin
     // wk2: [0..3] n~, J~ of channel 0, [4..7] of channel 1, [8..10] / [11..13] products or M per channel
@@ -2016,7 +2135,7 @@ struct EngineT : Engine {
       fft3d_t<R, N>(wk.p, 1, +1, s, pf);
       TC_HIP(hipMemcpyAsync(LOC[sp] + 5 * NR, wk.p, NR * sizeof(cx<R>), hipMemcpyDeviceToDevice, s));
     }
-    TC_HIP(hipEventRecord(ev.e[2], s));
+    ev.rec(2, s);
 
     // ---- 2: occupied-occupied pass of each channel (h5 split by kernel channel)
     const bool need_occ = m.m3a2 || m.m3a4 || m.m3b2 || m.m3b5;
@@ -2074,7 +2193,7 @@ struct EngineT : Engine {
         hipLaunchKernelGGL((k_lattice3<R, N>), dim3(nblk(long(P) * NR)), dim3(256), 0, s, H3[sp], HL[sp], bm, long(P),
                            3 * NR, NR);
       });
-    TC_HIP(hipEventRecord(ev.e[3], s));
+    ev.rec(3, s);
 
     // ---- 3/4: target batches of each spin (partners of the same spin)
     const bool need_A = m.m2ax || m.m2bx1 || m.m2bx2 || m.m3a3 || m.m3a4 || m.m3b4 || m.m3b6;
@@ -2087,7 +2206,7 @@ struct EngineT : Engine {
         TC_HIP(hipMemsetAsync(acc.p, 0, size_t(kAccSlots) * T * NR * sizeof(cx<double>), s));
         TC_HIP(hipMemsetAsync(h4.p, 0, size_t(3) * T * NR * sizeof(cx<R>), s));
         Events bev(3);
-        TC_HIP(hipEventRecord(bev.e[0], s));
+        bev.rec(0, s);
         const double part = fb * nt * S;
         if (need_A) {
           const FusedArgs fa{P, nt, t0, S, chunk};
@@ -2121,7 +2240,7 @@ struct EngineT : Engine {
             });
           }
         }
-        TC_HIP(hipEventRecord(bev.e[1], s));
+        bev.rec(1, s);
         if (need_B) {
           // 3b6 and pass B share one z stage and one partner sum (as in the unpolarised path)
           const bool merged = need_A && m.m3b6;
@@ -2154,7 +2273,7 @@ struct EngineT : Engine {
                                nullptr, nullptr, gpart.p, nullptr, nullptr, nullptr, acc.p, nullptr);
           });
         }
-        TC_HIP(hipEventRecord(bev.e[2], s));
+        bev.rec(2, s);
         K(TC_K_OTHER, fb * 16.0 * nt + 8.0 * fd * nt, [&] {
           hipLaunchKernelGGL((k_local<R, N>), dim3(nblk(long(nt) * NR)), dim3(256), 0, s, PSI[sp], DD[sp], LOC[sp],
                              h4.p, t0, nt, P, m, acc.p, g.p);
@@ -2166,12 +2285,12 @@ struct EngineT : Engine {
           hipLaunchKernelGGL((k_gather<R>), dim3(nblk(long(nt) * npm)), dim3(256), 0, s, g.p, sh.boxidx.p, sh.npw.p,
                              nb, npm, t0, nt, 1.0 / double(NR), sh.out.p + sp * cofs, NR);
         });
-        TC_HIP(hipEventSynchronize(bev.e[2]));
+        bev.sync(2, s);
         msA += bev.ms(0, 1);
         msB += bev.ms(1, 2);
       }
     }
-    TC_HIP(hipEventRecord(ev.e[4], s));
+    ev.rec(4, s);
 
     // ---- 5: kinetic energy and FP64 corrections per channel
     K(TC_K_CORR, 0.0, [&] {
@@ -2181,8 +2300,8 @@ struct EngineT : Engine {
       TC_HIP(hipMemsetAsync(sh.ecorr.p, 0, size_t(4) * P * sizeof(double), s));
       if (need_corr(pb, m)) corrections_pol(s, sh, pb, m);
     });
-    TC_HIP(hipEventRecord(ev.e[5], s));
-    TC_HIP(hipEventSynchronize(ev.e[5]));
+    ev.rec(5, s);
+    ev.sync(5, s);
     if (pf && pf->on) pf->collect();
     stage_ms[0] = ev.ms(0, 1);
     stage_ms[1] = ev.ms(1, 2);
@@ -2435,6 +2554,10 @@ void upload_twiddles() {
 
 // ====================================================================== C ABI
 struct tc_ctx {
+  // caller allocators (tc_set_allocator), first so that they outlive every buffer they made; entries are
+  // never changed, each buffer frees through the one that made it
+  std::list<DevAlloc> allocs;
+  const DevAlloc* cur_alloc = nullptr;
   int device = 0;
   hipStream_t stream = nullptr;
   bool own_stream = false;
@@ -2464,12 +2587,20 @@ int fail(tc_ctx* c, int code, const std::string& m) {
   return code;
 }
 
+// Device memory of a call comes from the context's allocator (t_alloc) for the length of the call.
+struct AllocScope {
+  const DevAlloc* prev;
+  explicit AllocScope(const DevAlloc* a) : prev(t_alloc) { t_alloc = a; }
+  ~AllocScope() { t_alloc = prev; }
+};
+
 template <class F>
 int guard(tc_ctx* c, F&& f) {
   if (!c) return TC_ERR_ARG;
   try {
     c->err.clear();
     TC_HIP(hipSetDevice(c->device));
+    AllocScope as(c->cur_alloc);
     return f();
   } catch (const TcError& e) {
     return fail(c, e.code, e.msg);
@@ -2815,7 +2946,7 @@ int do_apply_band(tc_ctx* c, double* out_host, double* eps_host) {
     ts.c3b6[1] = -2.0 * kPi * pb.A[1];
   }
   double stage[6];
-  c->eng->prof = &c->prof;
+  c->eng->prof = t_arena ? nullptr : &c->prof;
   c->eng->apply(c->stream, sh, pb, stage, &ts);
   std::vector<double> out(size_t(2) * NTG * npm);
   TC_HIP(hipMemcpyAsync(out.data(), sh.bout.p, out.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
@@ -3236,7 +3367,7 @@ void run_apply(tc_ctx* c, void* out_dev, double* out_host) {
   Shared& sh = c->sh;
   const int P = pb.nspin * pb.P();   // orbitals of all spin channels (spin-major)
   alloc_shared(c);
-  c->eng->prof = &c->prof;
+  c->eng->prof = t_arena ? nullptr : &c->prof;
   if (pb.nsym > 0)
     c->eng->apply_sym(c->stream, sh, pb, c->stage_ms);
   else
@@ -3282,7 +3413,7 @@ int do_apply_vectors(tc_ctx* c, int nvec, const double* in_dev, double* out_dev)
   ts.nvec = nvec;
   ts.out = out_dev;
   double stage[6];
-  c->eng->prof = &c->prof;
+  c->eng->prof = t_arena ? nullptr : &c->prof;
   c->eng->apply(c->stream, c->sh, c->pb, stage, &ts);
   TC_HIP(hipStreamSynchronize(c->stream));
   return TC_OK;
@@ -3952,6 +4083,7 @@ int tc_apply_all_dev(tc_ctx* c, void* out_dev) {
   return guard(c, [&]() -> int { return do_apply(c, out_dev, nullptr); });
 }
 
+
 int tc_scf(tc_ctx* c, const tc_scf_params* prm, double* energies, int* iterations) {
   return guard(c, [&]() -> int {
     if (!prm) return fail(c, TC_ERR_ARG, "null parameters");
@@ -4084,6 +4216,29 @@ int tc_set_pair_store(tc_ctx* c, int on) {
     return TC_OK;
   });
 }
+
+int tc_set_allocator(tc_ctx* c, void* (*alloc_fn)(size_t, void*), void (*free_fn)(void*, size_t, void*), void* user) {
+  return guard(c, [&]() -> int {
+    if ((alloc_fn == nullptr) != (free_fn == nullptr))
+      return fail(c, TC_ERR_ARG, "give both an allocation and a release function, or neither");
+    if (!alloc_fn) {
+      c->cur_alloc = nullptr;
+      return TC_OK;
+    }
+    c->allocs.push_back(DevAlloc{alloc_fn, free_fn, user, c->stream});
+    c->cur_alloc = &c->allocs.back();
+    return TC_OK;
+  });
+}
+
+int tc_set_memory_budget(tc_ctx* c, size_t bytes) {
+  return guard(c, [&]() -> int {
+    c->pb.mem_budget = bytes;
+    return TC_OK;
+  });
+}
+
+void* tc_get_stream(const tc_ctx* c) { return c ? reinterpret_cast<void*>(c->stream) : nullptr; }
 
 int tc_set_profiling(tc_ctx* c, int on) {
   return guard(c, [&]() -> int {
