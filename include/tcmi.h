@@ -253,6 +253,17 @@ int tc_apply_all(tc_ctx* ctx, double* out);
  * the result then stays inside the context).  Asynchronous on the stream. */
 int tc_apply_all_dev(tc_ctx* ctx, void* out_dev);
 
+/* tc_apply_all_dev for callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation): this call makes no hipMalloc, hipFree or other
+ * allocation.  Every device buffer it needs (fields, pair buffers, partials, correction work areas, the
+ * output staging) is carved from a fixed scratch array of 256 MiB that each device holds from the
+ * library's load until the process ends; the context's own buffers are left as they were.  Problems
+ * whose buffers do not fit, even at one target per batch, return TC_ERR_OOM (tc_set_batch can lower the
+ * batch); the resident pair store is never used.  The context must have run an ordinary application
+ * (tc_apply_all_dev or tc_apply_all) since its last setter or load, else TC_ERR_STATE; out_dev must not
+ * be NULL (TC_ERR_ARG).  Synchronous.  All contexts on one device share its scratch, which keeps the last
+ * call's contents: calls that overlap in time on one device (other threads, other streams) race. */
+int tc_apply_all_dev_noalloc(tc_ctx* ctx, void* out_dev);
 
 /* Pseudo-energy per cell (reading of Eqs. EtotTC / EtotBiTC: (1/N_k) Re sum_{sigma,k,mu}
  * f <chi| T + h2/2 + h3/3 |phi>, chi = phi in TC mode) of the last application (runs

@@ -92,6 +92,7 @@ def lib():
         "tc_load_orbitals_dev": (I, [P, I, I, P, dp]),
         "tc_apply_all": (I, [P, dp]),
         "tc_apply_all_dev": (I, [P, P]),
+        "tc_apply_all_dev_noalloc": (I, [P, P]),
         "tc_energy": (I, [P, dp, dp]),
         "tc_energy_backward": (I, [P, dp, dp, dp]),
         "tc_energy_backward_dev": (I, [P, P, dp, dp]),
@@ -295,6 +296,11 @@ class TCOperator:
     def apply_dev(self, out_ptr: Optional[int] = None):
         self._check(self._L.tc_apply_all_dev(self._h, ctypes.c_void_p(out_ptr) if out_ptr else None),
                     "tc_apply_all_dev")
+
+    def apply_dev_noalloc(self, out_ptr: int):
+        """tc_apply_all_dev_noalloc: the same application with every device buffer from the library's fixed
+        scratch (needs one ordinary application on this context since its last change)."""
+        self._check(self._L.tc_apply_all_dev_noalloc(self._h, ctypes.c_void_p(out_ptr)), "tc_apply_all_dev_noalloc")
 
     def energy(self):
         e = np.zeros(1)

@@ -2553,11 +2553,51 @@ void upload_twiddles() {
 }  // namespace
 
 // ====================================================================== C ABI
+// Scratch of tc_apply_all_dev_noalloc: every device buffer of that call is carved from it (Arena).  Each
+// device that loads the library holds its own copy until the process ends.  Host code reaches it only
+// through the address hipGetSymbolAddress returns on each device (scratch_on), never through the name.
+constexpr size_t kNoAllocScratchBytes = size_t(256) << 20;
+static __device__ __align__(256) char scratch[kNoAllocScratchBytes];
+
+namespace {
+std::mutex g_scratch_mu;
+std::unordered_map<int, char*> g_scratch;   // device -> address of its scratch
+
+// Address of `scratch` on `device`, which must be the current device; looked up once per device.
+char* scratch_on(int device) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch.find(device);
+  if (it != g_scratch.end()) return it->second;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr)
+    throw TcError(TC_ERR_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+  g_scratch[device] = static_cast<char*>(ptr);
+  return static_cast<char*>(ptr);
+}
+
+// For the length of a no-allocation call: device buffers are carved from the scratch (Arena), and
+// every buffer rebound or hidden during the call gets its previous state back at the end.
+struct ArenaScope {
+  Arena arena;
+  explicit ArenaScope(char* base) {
+    arena.base = base;
+    arena.cap = kNoAllocScratchBytes;
+    t_arena = &arena;
+  }
+  ~ArenaScope() {
+    t_arena = nullptr;
+    for (auto it = arena.undo.rbegin(); it != arena.undo.rend(); ++it) (*it)();
+  }
+};
+}  // namespace
+
 struct tc_ctx {
   // caller allocators (tc_set_allocator), first so that they outlive every buffer they made; entries are
   // never changed, each buffer frees through the one that made it
   std::list<DevAlloc> allocs;
   const DevAlloc* cur_alloc = nullptr;
+  char* scratch = nullptr;   // this device's no-allocation scratch (set at tc_create)
   int device = 0;
   hipStream_t stream = nullptr;
   bool own_stream = false;
@@ -3400,6 +3440,24 @@ int do_apply(tc_ctx* c, void* out_dev, double* out_host) {
   return TC_OK;
 }
 
+// tc_apply_all_dev with every device buffer of the call carved from the scratch.  The context must have
+// been prepared by an ordinary application since its last change (kernel tables and engine exist), so
+// that nothing outside the call's own buffers is made.
+int do_apply_noalloc(tc_ctx* c, void* out_dev) {
+  Problem& pb = c->pb;
+  if (!out_dev) return fail(c, TC_ERR_ARG, "out_dev must not be NULL");
+  if (!c->eng || c->tables_dirty || c->eng_prec != pb.prec || c->eng_N != pb.N || (pb.nsym > 0 && !pb.sym_ready))
+    return fail(c, TC_ERR_STATE,
+                "the context is not prepared: run tc_apply_all_dev (or tc_apply_all) once after the last change");
+  const int st = prepare(c);
+  if (st != TC_OK) return st;
+  if (!c->scratch) return fail(c, TC_ERR_DEVICE, "no scratch on this device");
+  TC_HIP(hipStreamSynchronize(c->stream));   // the scratch is free: the previous call on this stream is done
+  ArenaScope scope(c->scratch);
+  run_apply(c, out_dev, nullptr);
+  return TC_OK;
+}
+
 // The operator of the loaded orbitals applied to nvec trial vectors per k-point (device in/out).
 int do_apply_vectors(tc_ctx* c, int nvec, const double* in_dev, double* out_dev) {
   if (nvec <= 0) return fail(c, TC_ERR_ARG, "nvec must be positive");
@@ -3828,6 +3886,7 @@ int tc_create(int device, void* stream, tc_ctx** out) {
       c->own_stream = true;
     }
     upload_twiddles();
+    c->scratch = scratch_on(device);
     return TC_OK;
   });
   if (st != TC_OK) {
@@ -4083,6 +4142,9 @@ int tc_apply_all_dev(tc_ctx* c, void* out_dev) {
   return guard(c, [&]() -> int { return do_apply(c, out_dev, nullptr); });
 }
 
+int tc_apply_all_dev_noalloc(tc_ctx* c, void* out_dev) {
+  return guard(c, [&]() -> int { return do_apply_noalloc(c, out_dev); });
+}
 
 int tc_scf(tc_ctx* c, const tc_scf_params* prm, double* energies, int* iterations) {
   return guard(c, [&]() -> int {
