@@ -1,16 +1,19 @@
 """Benchmark of the transcorrelated-operator hot path on one MI355X.
 
 A step is one full application of the two- and three-body TC operator (all
-terms, SCF-mesh divergence corrections, energy) to every occupied orbital of
-the diamond-lattice silicon-like workload: fcc a = 10.26 bohr, 4x4x4 Gamma-centred
-k-mesh, 4 occupied bands, ~300 plane waves per k, 24^3 FFT grid (65,536
-same-spin orbital pairs).  The orbital coefficients are resident in HBM before
-the timed region; each step runs G->r, the Hartree-type fields, the
+terms, SCF-mesh divergence corrections, energy) to every occupied orbital.  The
+default workload is the largest single-GPU configuration: the 2x2x2 supercell of
+the diamond-lattice silicon-like cell (16 atoms, fcc a = 10.26 bohr), 2x2x2
+Gamma-centred k-mesh, 32 occupied bands, ~2400 plane waves per k, 48^3 FFT grid
+(65,536 same-spin orbital pairs).  The 4x4x4-k-mesh cell on the 24^3 grid (also
+65,536 pairs) is timed beside it.  The orbital coefficients are resident in HBM
+before the timed region; each step runs G->r, the Hartree-type fields, the
 occupied-occupied pass, passes A and B, r->G, the FP64 corrections and the
 energy reductions.
 
 Prints one JSON line (rank 0).  Metric: orbital-pair TC applications per
-second = N_pairs / (seconds per step).
+second = N_pairs / (seconds per step), and the TC energy's error against the
+FP64 oracle on a sample of the same cell and grid.
 """
 from __future__ import annotations
 
@@ -29,10 +32,9 @@ HBM_PEAK_GBS = 8000.0
 
 # HBM bytes per launch of a kernel, from two rocprofv3 counter passes (FETCH_SIZE, then WRITE_SIZE) over
 # one bench step, each scaled by what the counter reads for a plain 1 GiB device copy (FETCH x2, WRITE x1),
-# averaged over the launches of the step.  Keyed by kernel and by the hash of the library sources the
-# counters were taken on: any later change to those sources makes the figure stale (reported as null).
+# averaged over the launches of the step.  Keyed by workload, kernel and the hash of the library sources
+# the counters were taken on: any later change to those sources makes the figure stale (reported as null).
 MEASURED_TRAFFIC = {
-    ("k_fused_A<float,24>", "9a793a315a427a1f"): 3.5778e+10,
 }
 
 
@@ -49,6 +51,15 @@ def source_hash() -> str:
     with open(os.path.join(HERE, "include", "tcmi.h"), "rb") as fh:
         h.update(fh.read())
     return h.hexdigest()[:16]
+
+
+def describe(w) -> str:
+    """The cell of a named workload in words."""
+    if w.name.startswith("fcc_si_x2"):
+        return "2x2x2 supercell (16 atoms) of the fcc a=10.26 bohr silicon-like cell"
+    if w.name.startswith("fcc_si"):
+        return "fcc a=10.26 bohr silicon-like cell (2 atoms)"
+    return f"simple-cubic electron gas, {w.nelec_cell} electrons"
 
 
 def log(*a):
@@ -127,16 +138,27 @@ def time_steps(op, out, steps, warmup, profile=False):
     return ms, wall / steps * 1e3, energies, stats
 
 
-def cpu_baseline(budget_s: float):
-    """The FP64 oracle as it stands on a bounded sample of the workload (same cell,
-    grid, bands and Jastrow; 2x2x2 k-mesh = 32 orbitals per spin, 1024 same-spin pairs)."""
-    import torch
+def oracle_sample(workload: str):
+    """A bounded sample of the workload that the FP64 oracle finishes in 10-30 s: the same cell, grid,
+    Jastrow and basis cut, fewer orbital pairs."""
     import tcinputs as T
+
+    if workload == "fcc_si_x2_k222_g48":
+        # the 16-atom supercell on the 48^3 grid at Gamma only, 16 of its bands (256 pairs)
+        w = T.fcc_si(kmesh=(1, 1, 1), grid=48, nb=16, supercell=2, seed_offset=4)
+        return w, "2x2x2 supercell (16 atoms), 48^3 grid, ~2400 plane waves, Gamma only, 16 bands"
+    # the cell on the 24^3 grid with a 2x2x2 k-mesh (1,024 pairs)
+    return T.fcc_si(kmesh=(2, 2, 2)), "fcc a=10.26 bohr cell, 24^3 grid, 4 bands, 2x2x2 k-mesh"
+
+
+def cpu_baseline(workload: str):
+    """The FP64 oracle as it stands, timed on a bounded sample of the workload (oracle_sample)."""
+    import torch
     from oracle.fftroute import Problem
 
     cores = len(os.sched_getaffinity(0))
     torch.set_num_threads(cores)
-    w = T.fcc_si(kmesh=(2, 2, 2))
+    w, what = oracle_sample(workload)
     t = time.perf_counter()
     with torch.no_grad():
         pr = Problem(w)
@@ -148,8 +170,7 @@ def cpu_baseline(budget_s: float):
         "unit": "orbital-pair TC applications/s",
         "cores": torch.get_num_threads(),
         "kind": "oracle",
-        "sample": f"fcc a=10.26 bohr cell, 24^3 grid, 4 bands, 2x2x2 k-mesh ({npairs} same-spin pairs, all terms, "
-                  f"both spins, energy {E:.10f} Ha); {dt:.1f} s",
+        "sample": f"{what} ({npairs} same-spin pairs, all terms, both spins, energy {E:.10f} Ha); {dt:.1f} s",
         "seconds": dt,
         "energy_Ha": E,
         "_workload": w,
@@ -184,8 +205,9 @@ def main():
     ap.add_argument("--no-scf", action="store_true", help="skip the block-Davidson SCF side measurement")
     ap.add_argument("--no-sym", action="store_true", help="skip the crystal-symmetry side measurement")
     ap.add_argument("--no-band", action="store_true", help="skip the band k-point side measurement")
-    ap.add_argument("--workload", default="fcc_si_k444_g24",
-                    help="named workload: fcc_si_k444_g24 (default), heg14_g16, heg54_twist2_g32, fcc_si_x2_k222_g48")
+    ap.add_argument("--workload", default="fcc_si_x2_k222_g48",
+                    help="named workload: fcc_si_x2_k222_g48 (default), fcc_si_k444_g24, heg14_g16, heg54_twist2_g32")
+    ap.add_argument("--no-g24", action="store_true", help="skip the 24^3 cell timed beside the headline")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB first (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -233,16 +255,34 @@ def main():
     fp64 = None
     if not args.no_fp64:
         op64, keep64 = make_op(w, tc.TC_PREC_FP64, stream)
-        ms64, wall64, e64, _ = time_steps(op64, out, max(1, min(args.steps, 2)), 1)
+        ms64, wall64, e64, _ = time_steps(op64, out, 1 if w.grid[0] >= 48 else max(1, min(args.steps, 2)), 1)
         E64 = e64[-1][0]
         fp64 = {"value": w.npairs / (ms64 / 1e3), "ms_per_step": ms64, "energy_Ha": E64}
         log(f"fp64: {ms64:.2f} ms/step, E = {E64:.12f}")
         op64.close()
         del keep64
 
+    g24 = None
+    if not args.no_g24 and args.workload != "fcc_si_k444_g24":
+        # the 4x4x4-k-mesh cell on the 24^3 grid (65,536 pairs), FP32, the headline's step and warm-up counts
+        w24 = T.workload("fcc_si_k444_g24")
+        out24 = torch.empty((w24.nk, w24.nband, max(m.shape[0] for m in w24.miller)), dtype=torch.complex128,
+                            device="cuda")
+        op24, keep24 = make_op(w24, tc.TC_PREC_FP32, stream)
+        ms24, _, e24, st24 = time_steps(op24, out24, args.steps, args.warmup, profile=True)
+        dom24 = max(st24.items(), key=lambda kv: kv[1]["ms"])
+        g24 = {"workload": w24.name, "value": w24.npairs / (ms24 / 1e3), "ms_per_step": ms24, "energy_Ha": e24[-1][0],
+               "dominant_kernel": dom24[0].replace("<R,N", "<float,24"),
+               "dominant_kernel_GBps": dom24[1]["bytes"] / (dom24[1]["ms"] * 1e-3) / 1e9,
+               "kernels_ms_per_step": {k: v["ms"] / args.steps for k, v in st24.items() if v["ms"] > 0}}
+        log(f"fcc_si_k444_g24 fp32: {ms24:.2f} ms/step, E = {e24[-1][0]:.12f}")
+        op24.close()
+        del keep24, out24
+
     bitc = None
-    if not args.no_bitc and args.workload == "fcc_si_k444_g24":
+    if not args.no_bitc:
         wb = T.workload("fcc_si_k444_g24_bitc")
+        out = torch.empty((wb.nk, wb.nband, max(m.shape[0] for m in wb.miller)), dtype=torch.complex128, device="cuda")
         res_b = {}
         for name, prec, nst in (("fp32", tc.TC_PREC_FP32, args.steps), ("fp64", tc.TC_PREC_FP64, 1)):
             op_b = make_op_bitc(wb, prec, stream)
@@ -257,10 +297,10 @@ def main():
         log(f"bitc fp32: {ms_b:.2f} ms/step, E = {e_b:.12f}; fp64 {res_b['fp64'][0]:.2f} ms/step")
 
     scf = None
-    if not args.no_scf and args.workload == "fcc_si_k444_g24":
+    if not args.no_scf:
         # three block-Davidson iterations (pmax = 2: three applications to 256 trial vectors each, the
         # subspace diagonalisation, and the energy of the new orbitals) from the workload's orbitals
-        op_c, keep_c = make_op(w, tc.TC_PREC_FP32, stream)
+        op_c, keep_c = make_op(T.workload("fcc_si_k444_g24"), tc.TC_PREC_FP32, stream)
         op_c.energy()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -274,11 +314,12 @@ def main():
         del keep_c
 
     sym = None
-    if not args.no_sym and args.workload == "fcc_si_k444_g24":
+    if not args.no_sym:
         # the same cell with orbitals invariant under the diamond structure's 48 operations: the
         # symmetry-reduced path (occupied-occupied rows and targets at the 8 representative k-points of
         # 64) against the unreduced path on the same inputs
         ws = T.workload("fcc_si_k444_g24_sym")
+        out = torch.empty((ws.nk, ws.nband, max(m.shape[0] for m in ws.miller)), dtype=torch.complex128, device="cuda")
         ops = T.diamond_ops(ws.lattice)
         res_y = {}
         for name, prec, sops, nst in (("sym_fp32", tc.TC_PREC_FP32, ops, args.steps),
@@ -298,7 +339,7 @@ def main():
         log(f"symmetry fp32: {ms_y:.2f} ms/step vs unreduced {res_y['full_fp32'][0]:.2f} ms/step, E = {e_y:.12f}")
 
     band = None
-    if not args.no_band and args.workload == "fcc_si_k444_g24":
+    if not args.no_band:
         # band structure: the operator of the mesh orbitals applied to 4 orbitals at each of 16 k-points on
         # L - Gamma - X (off the mesh), with the band forms of the divergence corrections; one application
         # includes the mesh densities and occupied-occupied pass
@@ -338,7 +379,7 @@ def main():
     kname = name.replace("<R,N", "<float,%d" % w.grid[0])
     shash = source_hash()
     roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-            "traffic": MEASURED_TRAFFIC.get((kname, shash)) if args.workload == "fcc_si_k444_g24" else None, "kernel": kname,
+            "traffic": MEASURED_TRAFFIC.get((args.workload, kname, shash)), "kernel": kname,
             "avg_launch_ms": avg_ms, "algorithmic_bytes_per_launch": avg_bytes,
             "launches_per_step": st["launches"] / args.steps, "source_hash": shash}
     per_kernel = {k: {"ms_per_step": v["ms"] / args.steps,
@@ -348,7 +389,7 @@ def main():
     cpu = None
     if not args.no_cpu:
         try:
-            cpu = cpu_baseline(30.0)
+            cpu = cpu_baseline(args.workload)
             log(f"cpu oracle: {cpu['value']:.3f} pairs/s on {cpu['cores']} threads ({cpu['seconds']:.1f} s)")
         except Exception as e:  # the baseline is reported, never required
             log(f"cpu baseline failed: {e!r}")
@@ -373,7 +414,7 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {
-            "workload": f"{w.name}: fcc a=10.26 bohr silicon-like cell, {w.kmesh[0]}x{w.kmesh[1]}x{w.kmesh[2]} "
+            "workload": f"{w.name}: {describe(w)}, {w.kmesh[0]}x{w.kmesh[1]}x{w.kmesh[2]} "
                         f"Gamma-centred k-mesh, {w.nband} occupied bands, "
                         f"{sum(m.shape[0] for m in w.miller) / w.nk:.1f} plane waves/k, {w.grid[0]}^3 grid, "
                         f"all two- and three-body TC terms + SCF-mesh GB corrections + energy",
@@ -389,6 +430,7 @@ def main():
         "fp32_splitbf16_gpu": dict(split, energy_rel_err_vs_fp64=(abs(split["energy_Ha"] - fp64["energy_Ha"])
                                                                   / abs(fp64["energy_Ha"])) if fp64 else None)
         if split else None,
+        "fcc_si_k444_g24_fp32_gpu": g24,
         "bitc_fp32_gpu": bitc,
         "scf_davidson_gpu": scf,
         "symmetry_fp32_gpu": sym,

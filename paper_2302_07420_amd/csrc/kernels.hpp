@@ -413,6 +413,38 @@ __device__ __forceinline__ int sigma48(int k) {
   return r >= 48 ? r - 48 : r;
 }
 
+// One 16-point comb n1 of a 48-point line in LDS (element stride ST), transformed in place.
+template <typename R, int DIR, int N1, int ST>
+__device__ __forceinline__ void comb16(cx<R>* line) {
+  cx<R> v[16];
+#pragma unroll
+  for (int n2 = 0; n2 < 16; ++n2) v[n2] = line[((16 * N1 + 3 * n2) % 48) * ST];
+  fft_pow2<R, 16, DIR>(v);
+#pragma unroll
+  for (int n2 = 0; n2 < 16; ++n2) line[((16 * N1 + 3 * n2) % 48) * ST] = v[n2];
+}
+
+// The combs of np planes' lines along one axis, one (line, comb) per task: every thread of the
+// work-group takes part.  The comb index is uniform over most waves; it selects one of three
+// compile-time address patterns.
+template <typename R, int DIR, bool COL>
+__device__ __forceinline__ void comb_pass48(cx<R>* sm, int np, int tid, int nth) {
+  constexpr int N = 48, LD = N + 1, PL = N * LD;
+  const int nl = np * N;
+  for (int t = tid; t < 3 * nl; t += nth) {
+    const int n1 = t / nl, r = t - n1 * nl;
+    const int p = r / N, l = r - p * N;
+    cx<R>* line = COL ? sm + p * PL + l : sm + p * PL + l * LD;
+    if (n1 == 0)
+      comb16<R, DIR, 0, COL ? LD : 1>(line);
+    else if (n1 == 1)
+      comb16<R, DIR, 1, COL ? LD : 1>(line);
+    else
+      comb16<R, DIR, 2, COL ? LD : 1>(line);
+  }
+  __syncthreads();
+}
+
 // In-place 2D transform of np 48 x 48 planes in LDS ([np][48][49]) in three passes over the
 // prime-factor (Good-Thomas) structure 48 = 3 x 16, which has no twiddles between its factors:
 //   1. every row: the three 16-point transforms over n2 of its combs n1 (positions 16 n1 + 3 n2 mod 48);
@@ -423,39 +455,37 @@ __device__ __forceinline__ int sigma48(int k) {
 // Chinese-remainder map k = 16 k1 + 33 k2, so output k sits at sigma48(k) on each axis; with the input
 // at sigma48 positions the output is in natural order (the two maps swap roles).  A thread holds one
 // 16-point comb (32 registers in FP32) instead of a 48-point line.  Ends with a barrier.
-template <typename R, int DIR>
+// BAL: the row and column passes take one (line, comb) per task (comb_pass48); otherwise a thread takes a
+// whole line's three combs in turn (fewer threads busy, a shorter instruction stream), which measured
+// faster in k_fused_A and slower in k_fused_O and k_passB_xy.
+template <typename R, int DIR, bool BAL>
 __device__ __forceinline__ void planes_comb48(cx<R>* sm, int np, int tid, int nth) {
   constexpr int N = 48, LD = N + 1, PL = N * LD;
-  for (int t = tid; t < np * N; t += nth) {
-    const int p = t / N, y = t - p * N;
-    cx<R>* row = sm + p * PL + y * LD;
-#pragma unroll
-    for (int n1 = 0; n1 < 3; ++n1) {
-      cx<R> v[16];
-#pragma unroll
-      for (int n2 = 0; n2 < 16; ++n2) v[n2] = row[(16 * n1 + 3 * n2) % N];
-      fft_pow2<R, 16, DIR>(v);
-#pragma unroll
-      for (int n2 = 0; n2 < 16; ++n2) row[(16 * n1 + 3 * n2) % N] = v[n2];
+  if constexpr (BAL) {
+    comb_pass48<R, DIR, false>(sm, np, tid, nth);
+    comb_pass48<R, DIR, true>(sm, np, tid, nth);
+  } else {
+    for (int t = tid; t < np * N; t += nth) {
+      const int p = t / N, y = t - p * N;
+      cx<R>* row = sm + p * PL + y * LD;
+      comb16<R, DIR, 0, 1>(row);
       __builtin_amdgcn_sched_barrier(0);   // one comb in registers at a time
-    }
-  }
-  __syncthreads();
-  for (int t = tid; t < np * N; t += nth) {
-    const int p = t / N, x = t - p * N;
-    cx<R>* col = sm + p * PL + x;
-#pragma unroll
-    for (int n1 = 0; n1 < 3; ++n1) {
-      cx<R> v[16];
-#pragma unroll
-      for (int n2 = 0; n2 < 16; ++n2) v[n2] = col[((16 * n1 + 3 * n2) % N) * LD];
-      fft_pow2<R, 16, DIR>(v);
-#pragma unroll
-      for (int n2 = 0; n2 < 16; ++n2) col[((16 * n1 + 3 * n2) % N) * LD] = v[n2];
+      comb16<R, DIR, 1, 1>(row);
       __builtin_amdgcn_sched_barrier(0);
+      comb16<R, DIR, 2, 1>(row);
     }
+    __syncthreads();
+    for (int t = tid; t < np * N; t += nth) {
+      const int p = t / N, x = t - p * N;
+      cx<R>* col = sm + p * PL + x;
+      comb16<R, DIR, 0, LD>(col);
+      __builtin_amdgcn_sched_barrier(0);
+      comb16<R, DIR, 1, LD>(col);
+      __builtin_amdgcn_sched_barrier(0);
+      comb16<R, DIR, 2, LD>(col);
+    }
+    __syncthreads();
   }
-  __syncthreads();
   for (int t = tid; t < np * 256; t += nth) {
     const int p = t >> 8, ky = (t >> 4) & 15, kx = t & 15;
     cx<R>* pl = sm + p * PL;
@@ -494,10 +524,10 @@ __device__ __forceinline__ void planes_comb48(cx<R>* sm, int np, int tid, int nt
 // round's writes need no barrier between them: only the barrier before the next transform.  At N = 48
 // the transform is planes_comb48: reads after it use PlaneWG::ss (sigma order), and a barrier separates
 // them from the next round's writes (end_round).
-template <typename R, int N, int DIR>
+template <typename R, int N, int DIR, bool BAL = false>
 __device__ __forceinline__ void planes_fft(cx<R>* sm, int np, int tid) {
   if constexpr (Fz<R, N>::COMB) {
-    planes_comb48<R, DIR>(sm, np, tid, Fz<R, N>::NTH);
+    planes_comb48<R, DIR, BAL>(sm, np, tid, Fz<R, N>::NTH);
     return;
   }
   constexpr int LD = N + 1, RB = Fz<R, N>::RB;
@@ -707,7 +737,7 @@ k_passB_xy(const cx<R>* psi, const cx<R>* chi, const cx<R>* Zl, const cx<R>* Hl,
     }
     if (PF && q0 + NPQ < wg.qe) fetch(q0 + NPQ);
     __syncthreads();
-    planes_fft<R, N, -1>(sm, 3 * nq, threadIdx.x);
+    planes_fft<R, N, -1, true>(sm, 3 * nq, threadIdx.x);
     for (int a = 0; a < nq; ++a) {
       const int q = q0 + a;
       const double* del = dfr + 3 * pair_dindex(mi, int(jt), q, 1);
@@ -1510,7 +1540,7 @@ __global__ void __launch_bounds__((Fz<R, N>::NTH)) k_fused_O(const cx<R>* buf4, 
       }
       if (PF && q + 1 < wg.qe) fetch(q + 1);
       __syncthreads();
-      planes_fft<R, N, 1>(sm, SPLIT ? 3 : 6, threadIdx.x);
+      planes_fft<R, N, 1, true>(sm, SPLIT ? 3 : 6, threadIdx.x);
 #pragma unroll
       for (int i = 0; i < KP; ++i) {
         const long r = wg.zo + RB * N * i;
