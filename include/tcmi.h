@@ -275,7 +275,8 @@ int tc_energy(tc_ctx* ctx, double* e_total, double* e_parts);
  * corrections, Eqs. SCF / BITCSCF, without the kinetic term) to nvec trial vectors per k-point, as
  * the block-Davidson iteration of Sec. 2.4 needs.  in and out are [nk][nvec][npw_max] complex128,
  * vector v of k-point k at (k*nvec + v); input beyond npw(k) is ignored, output beyond it is zero.
- * Every term is linear in the target: the occupied set supplies the densities, partner sums and
+ * With two spin channels (tc_set_nspin) they are [2][nk][nvec][npw_max]: each channel's vectors
+ * against that channel's operator (Eq. SCF per spin).  Every term is linear in the target: the occupied set supplies the densities, partner sums and
  * corrections, and the trial vectors take the target role (phi_j in the algorithms).  The results of
  * the last tc_apply_all* (energies, orbital energies) are not changed.  TC_ERR_ARG for nvec <= 0 or
  * null buffers. */
@@ -319,6 +320,10 @@ int tc_scf(tc_ctx* ctx, const tc_scf_params* prm, double* energies, int* iterati
  * NULL) and, in the biorthogonal mode, left (NULL, or TC_ERR_STATE without left orbitals). */
 int tc_get_orbitals(tc_ctx* ctx, int ik, double* right, double* left);
 
+/* The same for spin channel `spin` (0 or 1 with tc_set_nspin(ctx, 2); left only for channel 0).
+ * TC_ERR_ARG for a channel out of range. */
+int tc_get_orbitals_spin(tc_ctx* ctx, int spin, int ik, double* right, double* left);
+
 /* Orbital energies of the last application (runs one if needed): eps receives [nk][nband]
  * complex128, eps_j = <chi_j| T + h2 + h3 |phi_j> with the selected terms and corrections (the
  * diagonal elements of Eqs. SCF / BITCSCF, chi = phi in TC mode; Re eps_jj is the one-electron
@@ -329,7 +334,8 @@ int tc_orbital_energies(tc_ctx* ctx, double* eps);
 /* Gradient of the pseudo-energy of the loaded orbitals (the functional returned by
  * tc_energy, with the selected terms and corrections).  grad (host, may be NULL)
  * receives [nk][nband][npw_max] complex128 dE/dRe c + i dE/dIm c = 2 dE/dc* for the
- * coefficients shared by both spin channels, zero-padded like tc_apply_all; dA and
+ * coefficients shared by both spin channels, zero-padded like tc_apply_all (with two
+ * channels, tc_set_nspin: [2][nk][nband][npw_max], each channel's own coefficients); dA and
  * dC (may be NULL) receive dE/dA_s and dE/dC_s (s = parallel, antiparallel) with the
  * four parameters independent.  Both are exact derivatives of the discrete energy:
  * the orbital gradient comes from one extra application whose scalar kernel is
@@ -385,10 +391,12 @@ int tc_set_batch(tc_ctx* ctx, int targets_per_batch);
  * fits on the device with a quarter of its memory (at least 16 GiB) left free, those outputs are
  * computed once and kept, and the occupied-occupied pass reads its four fields per pair from them
  * (the pair (a, b) of that pass is the pass-A pair with target b and partner a: same density
- * conj(psi_a) psi_b, same momentum k_b - k_a) instead of recomputing them.  Otherwise, and with
- * on = 0, both passes transform their own pair densities.  Results do not depend on it; the store
- * is released when it is switched off.  Biorthogonal mode, trial vectors, band k-points,
- * symmetry-reduced and spin-polarised runs always use the batched form. */
+ * conj(chi_a) psi_b, same momentum k_b - k_a; in the biorthogonal mode its second convolution, of
+ * conj(chi_b) psi_a at k_a - k_b, is the pass-A pair with target a and partner b) instead of
+ * recomputing them.  Otherwise, and with on = 0, both passes transform their own pair densities.
+ * Results do not depend on it; the store is released when it is switched off.  Trial vectors, band
+ * k-points, symmetry-reduced and spin-polarised runs always use the batched form.  With a budget
+ * (tc_set_memory_budget) the store is kept when it and 8 targets of pair buffers fit in it. */
 int tc_set_pair_store(tc_ctx* ctx, int on);
 
 /* Kernels timed by tc_kernel_stats (device time between HIP events recorded on the

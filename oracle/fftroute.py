@@ -119,13 +119,14 @@ class Problem:
     """One (possibly spin-unpolarized) TC / BITC problem on a uniform k-mesh.
 
     ``coeff`` / ``left`` override the workload's coefficients (per k, (nb,npw)
-    complex128 torch tensors, possibly requiring grad); ``A`` / ``C`` are
+    complex128 torch tensors, possibly requiring grad); ``coeff_dn`` those of the
+    down-spin channel of a spin-polarised workload; ``A`` / ``C`` are
     2-element float64 tensors (parallel, antiparallel), possibly requiring grad.
     Both spin channels use the same orbitals (unpolarized input).
     """
 
     def __init__(self, w, A=None, C=None, coeff=None, left=None, div_correction=True,
-                 alpha=None, biorthogonalize=True, reading="printed"):
+                 alpha=None, biorthogonalize=True, reading="printed", coeff_dn=None):
         self.w = w
         self.lattice = np.asarray(w.lattice, dtype=np.float64)
         self.omega = abs(float(np.linalg.det(self.lattice)))
@@ -180,7 +181,7 @@ class Problem:
         # spin channels (Sec. 2.1, Eq. SCF: one orbital set per spin; unpolarized input: the same set)
         self.polarized = getattr(w, "right_dn", None) is not None
         if self.polarized:
-            crd = [torch.as_tensor(c, dtype=CD) for c in w.right_dn]
+            crd = [torch.as_tensor(c, dtype=CD) for c in w.right_dn] if coeff_dn is None else list(coeff_dn)
             cld = None if w.left_dn is None else [torch.as_tensor(c, dtype=CD) for c in w.left_dn]
             if cld is not None and biorthogonalize:
                 crd, cld = biorthogonalize_coeffs(crd, cld)

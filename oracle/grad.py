@@ -13,6 +13,10 @@ are the partial derivatives with A_par, A_anti, C_par, C_anti independent.
 Biorthogonal mode (energy_and_grad_bitc): the gradients with respect to the right and the left
 coefficients of the energy Re sum f <chi| T + h2/2 + h3/3 |phi> (reading R8), with the pair taken
 as given (biorthonormalised once beforehand, not differentiated through).
+
+Spin-polarised input (energy_and_grad_polarized, TC mode): one orbital set per spin channel, so one
+gradient 2 dE/dc* per channel.  With two equal channels they add up to the unpolarised gradient, whose
+coefficients both channels share.
 """
 from __future__ import annotations
 
@@ -66,4 +70,26 @@ def energy_bitc(w, right, left, terms=ALL_TERMS, div_correction=True, reading="p
         pr = Problem(w, coeff=[torch.as_tensor(c, dtype=CD) for c in right],
                      left=[torch.as_tensor(c, dtype=CD) for c in left], div_correction=div_correction,
                      biorthogonalize=False, reading=reading)
+        return float(pr.energy(terms=terms))
+
+
+def energy_and_grad_polarized(w, terms=ALL_TERMS, div_correction=True, reading="printed"):
+    """(E, grad_up, grad_dn, dA, dC) of a spin-polarised workload (TC mode)."""
+    up = [torch.as_tensor(c, dtype=CD).clone().requires_grad_(True) for c in w.right]
+    dn = [torch.as_tensor(c, dtype=CD).clone().requires_grad_(True) for c in w.right_dn]
+    A = torch.as_tensor(w.A, dtype=RD).clone().requires_grad_(True)
+    C = torch.as_tensor(w.C, dtype=RD).clone().requires_grad_(True)
+    pr = Problem(w, A=A, C=C, coeff=up, coeff_dn=dn, div_correction=div_correction, reading=reading)
+    E = pr.energy(terms=terms)
+    g = torch.autograd.grad(E, up + dn + [A, C])
+    nk = len(up)
+    return (float(E.detach()), [x.numpy() for x in g[:nk]], [x.numpy() for x in g[nk:2 * nk]],
+            g[-2].numpy(), g[-1].numpy())
+
+
+def energy_polarized(w, up=None, dn=None, A=None, C=None, terms=ALL_TERMS, div_correction=True):
+    with torch.no_grad():
+        pr = Problem(w, A=A, C=C, coeff=None if up is None else [torch.as_tensor(c, dtype=CD) for c in up],
+                     coeff_dn=None if dn is None else [torch.as_tensor(c, dtype=CD) for c in dn],
+                     div_correction=div_correction)
         return float(pr.energy(terms=terms))

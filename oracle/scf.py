@@ -39,16 +39,20 @@ def _kinetic_diag(w, k):
     return 0.5 * np.sum(kg * kg, 1)
 
 
-def operator_matrices(w, right, left=None, terms=ALL_TERMS, reading="printed"):
+def operator_matrices(w, right, left=None, terms=ALL_TERMS, reading="printed", spin=0, right_dn=None):
     """[T + h[phi]] on each k-point's plane-wave set, H[k][G', G] = <e_G'| T + h |e_G>.
 
     ``right``/``left``: per k (nb, npw) arrays, used as given (left already biorthonormal, or None);
-    ``reading``: the mesh corrections' reading of the FFT-route oracle (R4).
+    ``reading``: the mesh corrections' reading of the FFT-route oracle (R4).  Spin-polarised workloads
+    (TC mode): ``right_dn`` the down channel's orbitals (default the workload's), ``spin`` the channel
+    whose operator is returned; the unit vectors join both channels with zero filling.
     """
     nk = w.nk
     npw = [m.shape[0] for m in w.miller]
     nx = max(npw)
-    ext_r, ext_l, occ = [], [], []
+    pol = getattr(w, "right_dn", None) is not None
+    dn = (w.right_dn if right_dn is None else right_dn) if pol else None
+    ext_r, ext_l, occ, ext_d, occ_d = [], [], [], [], []
     for k in range(nk):
         E = np.zeros((nx, npw[k]), dtype=np.complex128)
         E[np.arange(npw[k]), np.arange(npw[k])] = 1.0
@@ -56,10 +60,17 @@ def operator_matrices(w, right, left=None, terms=ALL_TERMS, reading="printed"):
         if left is not None:
             ext_l.append(np.concatenate([left[k], E]))
         occ.append(np.concatenate([np.asarray(w.occ[k], dtype=np.float64), np.zeros(nx)]))
-    wx = w.replace(right=ext_r, left=ext_l if left is not None else None, occ=occ)
+        if pol:
+            ext_d.append(np.concatenate([dn[k], E]))
+            od = w.occ_dn if w.occ_dn is not None else w.occ
+            occ_d.append(np.concatenate([np.asarray(od[k], dtype=np.float64), np.zeros(nx)]))
+    if pol:
+        wx = w.replace(right=ext_r, left=None, occ=occ, right_dn=ext_d, left_dn=None, occ_dn=occ_d)
+    else:
+        wx = w.replace(right=ext_r, left=ext_l if left is not None else None, occ=occ)
     pr = Problem(wx, biorthogonalize=False, reading=reading)
-    g = sum(MULT.get(t, 1) * pr.term(t, 0) for t in terms)
-    hc = pr.to_coeff(g)
+    g = sum(MULT.get(t, 1) * pr.term(t, spin) for t in terms)
+    hc = pr.to_coeff(g, spin)
     nb = right[0].shape[0]
     out = []
     for k in range(nk):

@@ -88,6 +88,7 @@ def lib():
         "tc_scf": (I, [P, ctypes.POINTER(SCFParams), dp, ctypes.POINTER(I)]),
         "tc_energy_backward_lr": (I, [P, dp, dp, dp, dp]),
         "tc_get_orbitals": (I, [P, I, dp, dp]),
+        "tc_get_orbitals_spin": (I, [P, I, I, dp, dp]),
         "tc_apply_dev": (I, [P, I, P, P]),
         "tc_load_orbitals_dev": (I, [P, I, I, P, dp]),
         "tc_apply_all": (I, [P, dp]),
@@ -309,19 +310,23 @@ class TCOperator:
         return float(e[0]), dict(zip(E_PARTS, parts.tolist()))
 
     def apply_vectors(self, vecs) -> List[np.ndarray]:
-        """h v for trial vectors: ``vecs`` per k-point (nvec, npw(k)), the same nvec everywhere."""
-        nk = len(self.npw)
-        nvec = np.asarray(vecs[0]).shape[0]
-        buf = np.zeros((nk, nvec, self.npw_max), dtype=np.complex128)
-        for k in range(nk):
-            v = np.asarray(vecs[k], dtype=np.complex128)
-            if v.shape != (nvec, self.npw[k]):
-                raise ValueError(f"k-point {k}: vectors of shape {v.shape}, expected {(nvec, self.npw[k])}")
-            buf[k, :, : self.npw[k]] = v
+        """h v for trial vectors: ``vecs`` per k-point (nvec, npw(k)), the same nvec everywhere; with two spin
+        channels, one such list per channel (each against its own channel's operator)."""
+        nk, ns = len(self.npw), self.nspin
+        per = [vecs] if ns == 1 else list(vecs)
+        nvec = np.asarray(per[0][0]).shape[0]
+        buf = np.zeros((ns, nk, nvec, self.npw_max), dtype=np.complex128)
+        for sp in range(ns):
+            for k in range(nk):
+                v = np.asarray(per[sp][k], dtype=np.complex128)
+                if v.shape != (nvec, self.npw[k]):
+                    raise ValueError(f"k-point {k}: vectors of shape {v.shape}, expected {(nvec, self.npw[k])}")
+                buf[sp, k, :, : self.npw[k]] = v
         out = np.zeros_like(buf)
         self._check(self._L.tc_apply(self._h, nvec, _dp(buf.view(np.float64)), _dp(out.view(np.float64))),
                     "tc_apply")
-        return [out[k, :, : self.npw[k]].copy() for k in range(nk)]
+        res = [[out[sp, k, :, : self.npw[k]].copy() for k in range(nk)] for sp in range(ns)]
+        return res[0] if ns == 1 else res
 
     def apply_vectors_dev(self, nvec: int, in_ptr: int, out_ptr: int):
         """Device form of apply_vectors: [nk][nvec][npw_max] complex128 buffers (synchronous)."""
@@ -336,12 +341,18 @@ class TCOperator:
         self._check(self._L.tc_scf(self._h, ctypes.byref(prm), _dp(e), ctypes.byref(n)), "tc_scf")
         return e[: n.value].copy(), n.value
 
-    def get_orbitals(self, ik, left=False):
-        """Current orbitals of k-point ik: right (nband, npw), and left too when ``left``."""
+    def get_orbitals(self, ik, left=False, spin=None):
+        """Current orbitals of k-point ik: right (nband, npw), and left too when ``left``; ``spin`` selects the
+        channel with two spin channels."""
         r = np.zeros((self.nband, self.npw[ik]), dtype=np.complex128)
         l = np.zeros_like(r) if left else None
-        self._check(self._L.tc_get_orbitals(self._h, int(ik), _dp(r.view(np.float64)),
-                                            _dp(l.view(np.float64)) if left else None), "tc_get_orbitals")
+        if spin is None:
+            self._check(self._L.tc_get_orbitals(self._h, int(ik), _dp(r.view(np.float64)),
+                                                _dp(l.view(np.float64)) if left else None), "tc_get_orbitals")
+        else:
+            self._check(self._L.tc_get_orbitals_spin(self._h, int(spin), int(ik), _dp(r.view(np.float64)),
+                                                     _dp(l.view(np.float64)) if left else None),
+                        "tc_get_orbitals_spin")
         return (r, l) if left else r
 
     def orbital_energies(self) -> np.ndarray:
@@ -353,15 +364,19 @@ class TCOperator:
         return e.reshape(shape)
 
     def backward(self, want_grad=True, want_params=True):
-        """(grad per k as (nband, npw) complex128 = 2 dE/dc*, dE/dA (2,), dE/dC (2,)); unrequested parts are None."""
-        nk = len(self.npw)
-        g = np.zeros((nk, self.nband, self.npw_max), dtype=np.complex128) if want_grad else None
+        """(grad per k as (nband, npw) complex128 = 2 dE/dc*, dE/dA (2,), dE/dC (2,)); unrequested parts are None.
+        With two spin channels grad is [per k of spin 0, per k of spin 1]."""
+        nk, ns = len(self.npw), self.nspin
+        g = np.zeros((ns * nk, self.nband, self.npw_max), dtype=np.complex128) if want_grad else None
         dA = np.zeros(2) if want_params else None
         dC = np.zeros(2) if want_params else None
         self._check(self._L.tc_energy_backward(self._h, _dp(g.view(np.float64)) if want_grad else None,
                                                _dp(dA) if want_params else None, _dp(dC) if want_params else None),
                     "tc_energy_backward")
-        return ([g[k, :, : self.npw[k]] for k in range(nk)] if want_grad else None), dA, dC
+        if not want_grad:
+            return None, dA, dC
+        per = [[g[sp * nk + k, :, : self.npw[k]] for k in range(nk)] for sp in range(ns)]
+        return (per[0] if ns == 1 else per), dA, dC
 
     def backward_lr(self, want_right=True, want_left=True, want_params=True):
         """(grad_right, grad_left, dA, dC); biorthogonal mode: the two partial gradients (TC mode: the

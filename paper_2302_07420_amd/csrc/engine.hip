@@ -1326,8 +1326,8 @@ struct EngineT : Engine {
   }
 
   void apply(hipStream_t s, Shared& sh, const Problem& pb, double* stage_ms, const TargetSet* ts) override {
-    if (pb.nspin == 2) {   // spin-polarised (TC mode, orbitals as targets)
-      apply_pol(s, sh, pb, stage_ms);
+    if (pb.nspin == 2) {   // spin-polarised (TC mode; the orbitals or trial vectors of each channel as targets)
+      apply_pol(s, sh, pb, stage_ms, ts);
       return;
     }
     const int P = pb.P();
@@ -1347,7 +1347,7 @@ struct EngineT : Engine {
     // the occupied pass's.  When every pair's pass-A z-stage output fits on the device it is computed once,
     // before the occupied pass, which then reads it in place of its own pair densities and z stage.  (The
     // store is settled before the batch buffers, which take what it leaves of a caller's budget.)
-    const bool keepA = !pb.bitc && !ts && need_occ && need_A && pair_store(pb);
+    const bool keepA = !ts && need_occ && need_A && pair_store(pb);
     ensure(pb, pair_budget(pb));
     // targets: the orbitals, or nbt trial vectors per k-point
     const int nbt = ts ? ts->nvec : nb;
@@ -1474,7 +1474,19 @@ struct EngineT : Engine {
         const int nt = std::min(T, P - a0);
         const long npair = long(nt) * P;
         const FusedArgs fa{P, nt, a0, S, chunk};
-        if (keepA) {
+        if (keepA && bitc) {
+          // row a = a0 + t, partner b = q: V21 from the stored pair b P + a (density conj(chi_a) psi_b at
+          // k_b - k_a), V12 from the stored pair a P + b (conj(chi_b) psi_a at k_a - k_b), fields 1..4
+          K(TC_K_FUSED_OB, fb * (8.0 * npair + 2.0 * P) + 7.0 * fb * nt * S, [&] {
+            hipLaunchKernelGGL((k_fused_OB<R, N>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s,
+                               allB.p + (size_t(a0) * 5 + 1) * NR, allB.p + (size_t(a0) * 5 * P + 1) * NR, psi.p, X,
+                               sh.w.p, fa, mi, rc, dfr.p, h5cpart.p, H3part.p, Hbpart.p, 5L, 5L * P, 5L * P, 5L);
+          });
+          K(TC_K_SUM_PARTS, 7.0 * fb * nt * (S + 1), [&] {
+            hipLaunchKernelGGL((k_sum_parts_ob<R, N>), dim3(nblk(long(nt) * NR)), dim3(256), 0, s, S, nt, a0,
+                               h5cpart.p, H3part.p, Hbpart.p, h5c.p, H3a4.p, H3bc.p);
+          });
+        } else if (keepA) {
           // row a = a0 + t, partner b = q: fields 1..4 of the stored pair b P + a
           K(TC_K_FUSED_O, fb * (4.0 * npair + P) + 3.5 * fb * nt * S, [&] {
             hipLaunchKernelGGL((k_fused_O<R, N>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s,
@@ -2038,13 +2050,19 @@ struct EngineT : Engine {
   // pair orbitals of one spin; the Hartree-type fields, 3a2 (h6), 3b1, 3b2 and the 3b6 chain take the
   // parallel-channel kernels for the own spin and the antiparallel-channel ones for the other spin.
   // Layout: channel sp's coefficients, outputs and energies follow those of channel 0 (spin-major).
-  void apply_pol(hipStream_t s, Shared& sh, const Problem& pb, double* stage_ms) {
+  // ts: trial vectors of both channels ([2][nk][nvec][npw_max], channel-major, as the output); each channel's
+  // vectors take the target role against its own channel's partners
+  void apply_pol(hipStream_t s, Shared& sh, const Problem& pb, double* stage_ms, const TargetSet* ts = nullptr) {
     const int P = pb.P();
     const int nb = pb.nb;
     const int npm = pb.npw_max;
+    const int nbt = ts ? ts->nvec : nb;
+    const int NTG = pb.nk * nbt;
+    const size_t tcofs = size_t(2) * NTG * npm;   // doubles per channel of the trial vectors
     const Masks m = make_masks(pb.mask);
     ensure(pb, pair_budget(pb));
     const MeshInfo mi{pb.n1, pb.n2, pb.n3, nb, P, nb};
+    const MeshInfo miT{pb.n1, pb.n2, pb.n3, nb, P, nbt};   // target passes
     Recip rc;
     for (int i = 0; i < 9; ++i) rc.b[i] = pb.B[i];
     Basis<R> bm, mm;
@@ -2061,6 +2079,10 @@ struct EngineT : Engine {
       ProfScope ps(pf, s, id, bytes);
       launch();
     };
+    if (ts) {
+      psiT.alloc(size_t(NTG) * NR);
+      DT.alloc(size_t(3) * NTG * NR);
+    }
     cx<R>* PSI[2] = {psi.p, psi1.p};
     cx<R>* DD[2] = {D.p, D1.p};
     cx<R>* DL[2] = {Dl.p, Dl1.p};
@@ -2200,8 +2222,27 @@ struct EngineT : Engine {
     const bool need_B = m.m2bx2 || m.m3b3 || m.m3b4 || m.m3b5;
     for (int sp = 0; sp < 2; ++sp) {
       const int o = 1 - sp;
-      for (int t0 = 0; t0 < P; t0 += T) {
-        const int nt = std::min(T, P - t0);
+      const cx<R>* tP = PSI[sp];   // target fields: this channel's orbitals or trial vectors
+      const cx<R>* tD = DD[sp];
+      if (ts) {
+        TC_HIP(hipMemsetAsync(psiT.p, 0, size_t(NTG) * NR * sizeof(cx<R>), s));
+        TC_HIP(hipMemsetAsync(DT.p, 0, size_t(3) * NTG * NR * sizeof(cx<R>), s));
+        const unsigned gst = nblk(long(NTG) * npm);
+        const double* tc = ts->coef + sp * tcofs;
+        K(TC_K_SCATTER, 0.0, [&] {
+          hipLaunchKernelGGL((k_scatter<R>), dim3(gst), dim3(256), 0, s, tc, sh.boxidx.p, sh.npw.p, sh.kg.p, nbt, npm,
+                             NTG, -1, psiT.p, NR);
+          for (int c = 0; c < 3; ++c)
+            hipLaunchKernelGGL((k_scatter<R>), dim3(gst), dim3(256), 0, s, tc, sh.boxidx.p, sh.npw.p, sh.kg.p, nbt,
+                               npm, NTG, c, DT.p + size_t(c) * NTG * NR, NR);
+        });
+        fft3d_t<R, N>(psiT.p, NTG, +1, s, pf);
+        fft3d_t<R, N>(DT.p, 3L * NTG, +1, s, pf);
+        tP = psiT.p;
+        tD = DT.p;
+      }
+      for (int t0 = 0; t0 < NTG; t0 += T) {
+        const int nt = std::min(T, NTG - t0);
         const long npair = long(nt) * P;
         TC_HIP(hipMemsetAsync(acc.p, 0, size_t(kAccSlots) * T * NR * sizeof(cx<double>), s));
         TC_HIP(hipMemsetAsync(h4.p, 0, size_t(3) * T * NR * sizeof(cx<R>), s));
@@ -2212,14 +2253,14 @@ struct EngineT : Engine {
           const FusedArgs fa{P, nt, t0, S, chunk};
           K(TC_K_XY_PAIR_TGT, fb * (npair + nt + P), [&] {
             hipLaunchKernelGGL((k_pair_xy<R, N, false>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, PSI[sp],
-                               PSI[sp], fa, bufA.p);
+                               tP, fa, bufA.p);
           });
           K(TC_K_ZCONV_A1, fb * 6.0 * npair + tabB, [&] {
-            zconv<OP_A1>(s, npair, t0, mi, tb, 1);
+            zconv<OP_A1>(s, npair, t0, miT, tb, 1);
           });
           K(TC_K_FUSED_A, fb * ((m.m3b6 ? 9.0 : 5.0) * npair + 8.0 * P + nt) + 6.0 * part, [&] {
             hipLaunchKernelGGL((k_fused_A<R, N, true, false>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, bufB.p, PSI[sp],
-                               DL[sp], HL[sp], NJ[sp], W[sp], fa, m, int(m.m3b6 != 0), mi, bm, mm, dfr.p, bufA.p,
+                               DL[sp], HL[sp], NJ[sp], W[sp], fa, m, int(m.m3b6 != 0), miT, bm, mm, dfr.p, bufA.p,
                                gpart.p, h4part.p, NJ[o]);
           });
           K(TC_K_SUM_PARTS, 6.0 * part + 6.0 * fd * nt + 3.0 * fb * nt, [&] {
@@ -2228,7 +2269,7 @@ struct EngineT : Engine {
           });
           if (m.m3b6 && !need_B) {   // else shared with pass B below
             K(TC_K_ZCONV_A2, fb * 5.0 * npair + tabB, [&] {
-              zconv<OP_A2>(s, npair, t0, mi, tb, 1);
+              zconv<OP_A2>(s, npair, t0, miT, tb, 1);
             });
             K(TC_K_FUSED_Y, fb * (npair + P) + part, [&] {
               hipLaunchKernelGGL((k_fused_Y<R, N>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, bufB.p, PSI[sp],
@@ -2248,20 +2289,20 @@ struct EngineT : Engine {
           cx<R>* srcB = merged ? bufB.p : bufA.p;
           cx<R>* zout = merged ? bufB.p + size_t(2) * npair * NR : bufB.p;
           K(TC_K_OTHER, fb * 13.0 * nt, [&] {
-            hipLaunchKernelGGL((k_passB_Z<R, N>), dim3(nblk(long(nt) * NR)), dim3(256), 0, s, PSI[sp], DD[sp],
-                               LOC[sp] + NR, h4.p, t0, nt, P, m, bm, Z.p);
+            hipLaunchKernelGGL((k_passB_Z<R, N>), dim3(nblk(long(nt) * NR)), dim3(256), 0, s, tP, tD,
+                               LOC[sp] + NR, h4.p, t0, nt, NTG, m, bm, Z.p);
           });
           K(TC_K_XY_PASSB, fb * (2.0 * npair + 4.0 * P + 4.0 * nt), [&] {
-            hipLaunchKernelGGL((k_passB_xy<R, N>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, PSI[sp], PSI[sp], Z.p,
-                               HL[sp], fy, mi, dfr.p, R(m.m3b5), srcB);
+            hipLaunchKernelGGL((k_passB_xy<R, N>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, tP, PSI[sp], Z.p,
+                               HL[sp], fy, miT, dfr.p, R(m.m3b5), srcB);
           });
           if (merged) {
             K(TC_K_ZCONV_A2, fb * 7.0 * npair + tabB, [&] {
-              zconv<OP_A2>(s, bufA.p, zout, npair, t0, mi, tb, 1, bufB.p);
+              zconv<OP_A2>(s, bufA.p, zout, npair, t0, miT, tb, 1, bufB.p);
             });
           } else {
             K(TC_K_ZCONV_B, fb * 3.0 * npair + tabB, [&] {
-              zconv<OP_B>(s, npair, t0, mi, tb, 1);
+              zconv<OP_B>(s, npair, t0, miT, tb, 1);
             });
           }
           K(TC_K_FUSED_Y, fb * (npair + P) + part, [&] {
@@ -2275,15 +2316,16 @@ struct EngineT : Engine {
         }
         bev.rec(2, s);
         K(TC_K_OTHER, fb * 16.0 * nt + 8.0 * fd * nt, [&] {
-          hipLaunchKernelGGL((k_local<R, N>), dim3(nblk(long(nt) * NR)), dim3(256), 0, s, PSI[sp], DD[sp], LOC[sp],
-                             h4.p, t0, nt, P, m, acc.p, g.p);
-          hipLaunchKernelGGL((k_epart<R, N>), dim3(kAccSlots * nt), dim3(256), 0, s, PSI[sp], acc.p, t0, nt,
-                             sh.epart.p + size_t(kAccSlots) * sp * P);
+          hipLaunchKernelGGL((k_local<R, N>), dim3(nblk(long(nt) * NR)), dim3(256), 0, s, tP, tD, LOC[sp],
+                             h4.p, t0, nt, NTG, m, acc.p, g.p);
+          if (!ts)
+            hipLaunchKernelGGL((k_epart<R, N>), dim3(kAccSlots * nt), dim3(256), 0, s, PSI[sp], acc.p, t0, nt,
+                               sh.epart.p + size_t(kAccSlots) * sp * P);
         });
         fft3d_t<R, N>(g.p, nt, -1, s, pf);
         K(TC_K_OTHER, 0.0, [&] {
           hipLaunchKernelGGL((k_gather<R>), dim3(nblk(long(nt) * npm)), dim3(256), 0, s, g.p, sh.boxidx.p, sh.npw.p,
-                             nb, npm, t0, nt, 1.0 / double(NR), sh.out.p + sp * cofs, NR);
+                             nbt, npm, t0, nt, 1.0 / double(NR), ts ? ts->out + sp * tcofs : sh.out.p + sp * cofs, NR);
         });
         bev.sync(2, s);
         msA += bev.ms(0, 1);
@@ -2294,11 +2336,13 @@ struct EngineT : Engine {
 
     // ---- 5: kinetic energy and FP64 corrections per channel
     K(TC_K_CORR, 0.0, [&] {
-      for (int sp = 0; sp < 2; ++sp)
-        hipLaunchKernelGGL(k_kinetic, dim3(P), dim3(256), 0, s, sh.coef.p + sp * cofs, sh.coef.p + sp * cofs, sh.kg.p,
-                           sh.npw.p, nb, npm, sh.tkin.p + size_t(sp) * P);
-      TC_HIP(hipMemsetAsync(sh.ecorr.p, 0, size_t(4) * P * sizeof(double), s));
-      if (need_corr(pb, m)) corrections_pol(s, sh, pb, m);
+      if (!ts) {
+        for (int sp = 0; sp < 2; ++sp)
+          hipLaunchKernelGGL(k_kinetic, dim3(P), dim3(256), 0, s, sh.coef.p + sp * cofs, sh.coef.p + sp * cofs,
+                             sh.kg.p, sh.npw.p, nb, npm, sh.tkin.p + size_t(sp) * P);
+        TC_HIP(hipMemsetAsync(sh.ecorr.p, 0, size_t(4) * P * sizeof(double), s));
+      }
+      if (need_corr(pb, m)) corrections_pol(s, sh, pb, m, ts);
     });
     ev.rec(5, s);
     ev.sync(5, s);
@@ -2315,7 +2359,9 @@ struct EngineT : Engine {
   // 3a2 summed over the partner channel s2 with A_{pair(sp, s2)} (Eqs. divcor_3a2_first/second); 3b6
   // summed over the density channel s1 with A_{pair(s1, sp)} (Eqs. 3b6_div_scf1-3).  With identical
   // channels this is the unpolarised form.
-  void corrections_pol(hipStream_t s, Shared& sh, const Problem& pb, const Masks& m) {
+  // With a target set: the occupied-set quantities as above, and per channel the target-dependent ones
+  // (S(mu, v) = <c_mu|v>, O(mu, v) = <c_mu|F1 v>, W_v = FT(F2 v)) from that channel's trial vectors.
+  void corrections_pol(hipStream_t s, Shared& sh, const Problem& pb, const Masks& m, const TargetSet* ts = nullptr) {
     const int P = pb.P(), nb = pb.nb, nk = pb.nk, npm = pb.npw_max;
     const size_t cofs = size_t(2) * P * npm;
     cx<double>* PS64[2] = {psi64.p, psi64_1.p};
@@ -2386,12 +2432,42 @@ struct EngineT : Engine {
       const double c1s_p = 2 * kPi * corrB[0], c1s_a = 2 * kPi * corrB[1];
       const double const1 = c1a_p * cs[sp] + c1a_a * cs[o];
       const double c1sn0 = c1s_p * n0[sp] + c1s_a * n0[o];
-      hipLaunchKernelGGL(k_corr_apply, dim3(nblk(long(P) * npm)), dim3(256), 0, s, cf, cf, Ssp, sh.O.p, Zg, Wg,
-                         focc.p + sp * P, sh.npw.p, nb, nb, npm, P, pb.omega, 1.0, dgb_eff(pb, m, corrA[0]), m.m3a2,
-                         const1, 0.0,
-                         m.m3b6, c1sn0, 0.0, sh.dhc2.p + sp * cofs, sh.dhc3.p + sp * cofs);
-      hipLaunchKernelGGL(k_corr_add, dim3(P), dim3(256), 0, s, cf, sh.dhc2.p + sp * cofs, sh.dhc3.p + sp * cofs,
-                         sh.npw.p, nb, npm, sh.out.p + sp * cofs, sh.ecorr.p + size_t(2) * sp * P);
+      if (!ts) {
+        hipLaunchKernelGGL(k_corr_apply, dim3(nblk(long(P) * npm)), dim3(256), 0, s, cf, cf, Ssp, sh.O.p, Zg, Wg,
+                           focc.p + sp * P, sh.npw.p, nb, nb, npm, P, pb.omega, 1.0, dgb_eff(pb, m, corrA[0]), m.m3a2,
+                           const1, 0.0, m.m3b6, c1sn0, 0.0, sh.dhc2.p + sp * cofs, sh.dhc3.p + sp * cofs);
+        hipLaunchKernelGGL(k_corr_add, dim3(P), dim3(256), 0, s, cf, sh.dhc2.p + sp * cofs, sh.dhc3.p + sp * cofs,
+                           sh.npw.p, nb, npm, sh.out.p + sp * cofs, sh.ecorr.p + size_t(2) * sp * P);
+        continue;
+      }
+      // this channel's trial vectors as targets
+      const int nv = ts->nvec, NT = nk * nv;
+      const size_t nc = size_t(2) * NT * npm;
+      const double* tcf = ts->coef + sp * nc;
+      psiT64.alloc(size_t(NT) * NR);
+      prodT.alloc(size_t(2) * NT * NR);
+      for (auto* b : {&sh.ZgT, &sh.WgT, &sh.dhc2T, &sh.dhc3T}) b->alloc(nc);
+      sh.ST.alloc(size_t(2) * nk * nb * nv);
+      sh.OT.alloc(size_t(2) * nk * nb * nv);
+      sh.ecorrT.alloc(size_t(2) * NT);
+      TC_HIP(hipMemsetAsync(psiT64.p, 0, size_t(NT) * NR * sizeof(cx<double>), s));
+      hipLaunchKernelGGL((k_scatter<double>), dim3(nblk(long(NT) * npm)), dim3(256), 0, s, tcf, sh.boxidx.p, sh.npw.p,
+                         sh.kg.p, nv, npm, NT, -1, psiT64.p, NR);
+      fft3d_t<double, N>(psiT64.p, NT, +1, s);
+      hipLaunchKernelGGL((k_corr_products<N>), dim3(nblk(2L * NT * NR)), dim3(256), 0, s, F1, psiT64.p, NT, prodT.p);
+      fft3d_t<double, N>(prodT.p, 2L * NT, -1, s);
+      hipLaunchKernelGGL((k_gather<double>), dim3(nblk(long(NT) * npm)), dim3(256), 0, s, prodT.p, sh.boxidx.p,
+                         sh.npw.p, nv, npm, 0, NT, 1.0 / double(NR), sh.ZgT.p, NR);
+      hipLaunchKernelGGL((k_gather<double>), dim3(nblk(long(NT) * npm)), dim3(256), 0, s, prodT.p + size_t(NT) * NR,
+                         sh.boxidx.p, sh.npw.p, nv, npm, 0, NT, 1.0 / double(NR), sh.WgT.p, NR);
+      hipLaunchKernelGGL(k_overlap, dim3(nk * nb * nv), dim3(256), 0, s, cf, nb, tcf, nv, sh.npw.p, npm, nk, sh.ST.p);
+      hipLaunchKernelGGL(k_overlap, dim3(nk * nb * nv), dim3(256), 0, s, cf, nb, sh.ZgT.p, nv, sh.npw.p, npm, nk,
+                         sh.OT.p);
+      hipLaunchKernelGGL(k_corr_apply, dim3(nblk(long(NT) * npm)), dim3(256), 0, s, tcf, cf, sh.ST.p, sh.OT.p, Zg,
+                         sh.WgT.p, focc.p + sp * P, sh.npw.p, nb, nv, npm, NT, pb.omega, 1.0,
+                         dgb_eff(pb, m, corrA[0]), m.m3a2, const1, 0.0, m.m3b6, c1sn0, 0.0, sh.dhc2T.p, sh.dhc3T.p);
+      hipLaunchKernelGGL(k_corr_add, dim3(NT), dim3(256), 0, s, tcf, sh.dhc2T.p, sh.dhc3T.p, sh.npw.p, nv, npm,
+                         ts->out + sp * nc, sh.ecorrT.p);
     }
   }
 
@@ -2613,8 +2689,8 @@ struct tc_ctx {
   std::vector<double> eps;   // [P] complex orbital energies of the last application
   DBuf<double> coefT, outT;  // host-buffer tc_apply staging
   // block-Davidson self-consistent loop
-  DBuf<double> dV, dHV, dHs, dwork, dX, dY, deval, deps, dcur, dold, dnew, dmix, dchange;
-  DBuf<int> dvalid, dstatus;
+  DBuf<double> dV, dHV, dHs, dwork, dX, dY, deval, deps, dcur, dold, dnew, dmix, dchange, dkg2;
+  DBuf<int> dvalid, dstatus, dnpw2;
   double stage_ms[6] = {0, 0, 0, 0, 0, 0};
   double total_ms = 0;
   Prof prof;
@@ -3461,7 +3537,6 @@ int do_apply_noalloc(tc_ctx* c, void* out_dev) {
 // The operator of the loaded orbitals applied to nvec trial vectors per k-point (device in/out).
 int do_apply_vectors(tc_ctx* c, int nvec, const double* in_dev, double* out_dev) {
   if (nvec <= 0) return fail(c, TC_ERR_ARG, "nvec must be positive");
-  if (c->pb.nspin == 2) return fail(c, TC_ERR_UNSUPPORTED, "trial vectors are built for unpolarised runs");
   if (c->pb.nsym > 0) return fail(c, TC_ERR_UNSUPPORTED, "trial vectors are built without symmetry");
   int st = prepare(c);
   if (st != TC_OK) return st;
@@ -3501,7 +3576,6 @@ int do_backward(tc_ctx* c, void* grad_dev, double* grad_host, double* dA, double
     return fail(c, TC_ERR_UNSUPPORTED, "the gradient of the grad-u . grad terms needs 2ah and 2ax selected");
   int st = prepare(c);
   if (st != TC_OK) return st;
-  if (pb.nspin == 2) return fail(c, TC_ERR_UNSUPPORTED, "the gradient is built for unpolarised runs");
   if (pb.nsym > 0) return fail(c, TC_ERR_UNSUPPORTED, "the gradient is built without symmetry");
   if (!pb.bitc && (gl_dev || gl_host)) return fail(c, TC_ERR_ARG, "no left orbitals loaded: grad_left must be NULL");
   struct Keep {
@@ -3533,12 +3607,16 @@ int do_backward(tc_ctx* c, void* grad_dev, double* grad_host, double* dA, double
   Shared& sh = c->sh;
   const int P = pb.P();
   const size_t bytes = size_t(2) * P * pb.npw_max * sizeof(double);
+  // per spin channel (spin-major, as the operator output): scale w_p (h c_p + |k+G|^2/2 c_p)
   auto finish = [&](double scale, void* ddev, double* dhost) {
-    sh.grad.alloc(size_t(2) * P * pb.npw_max);
-    hipLaunchKernelGGL(k_grad_finish, dim3(nblk(long(P) * pb.npw_max)), dim3(256), 0, c->stream, sh.coef.p, sh.out.p,
-                       sh.kg.p, sh.npw.p, sh.w.p, pb.nb, pb.npw_max, P, scale, sh.grad.p);
-    if (ddev) TC_HIP(hipMemcpyAsync(ddev, sh.grad.p, bytes, hipMemcpyDeviceToDevice, c->stream));
-    if (dhost) TC_HIP(hipMemcpyAsync(dhost, sh.grad.p, bytes, hipMemcpyDeviceToHost, c->stream));
+    const size_t per = size_t(2) * P * pb.npw_max;   // doubles per channel
+    sh.grad.alloc(per * pb.nspin);
+    for (int sp = 0; sp < pb.nspin; ++sp)
+      hipLaunchKernelGGL(k_grad_finish, dim3(nblk(long(P) * pb.npw_max)), dim3(256), 0, c->stream,
+                         sh.coef.p + sp * per, sh.out.p + sp * per, sh.kg.p, sh.npw.p, sh.w.p + sp * P, pb.nb,
+                         pb.npw_max, P, scale, sh.grad.p + sp * per);
+    if (ddev) TC_HIP(hipMemcpyAsync(ddev, sh.grad.p, bytes * pb.nspin, hipMemcpyDeviceToDevice, c->stream));
+    if (dhost) TC_HIP(hipMemcpyAsync(dhost, sh.grad.p, bytes * pb.nspin, hipMemcpyDeviceToHost, c->stream));
     TC_HIP(hipStreamSynchronize(c->stream));
   };
   if (!pb.bitc) {
@@ -3548,7 +3626,9 @@ int do_backward(tc_ctx* c, void* grad_dev, double* grad_host, double* dA, double
       c->tables_dirty = true;
       c->eng->upload_tables(pb, TableVariant{TableVariant::GRADIENT, 0, 0.0});
       run_apply(c, nullptr, nullptr);
-      finish(4.0, grad_dev, grad_host);
+      // 2 dE/dc* = 2 w (T + h_grad) c per channel's own coefficients; unpolarised, both channels share
+      // them and the two contributions add (factor 4)
+      finish(pb.nspin == 2 ? 2.0 : 4.0, grad_dev, grad_host);
       pb.mask = m;
       pb.force_rem = false;
     }
@@ -3701,13 +3781,20 @@ int biorthogonalize(tc_ctx* c, int ik) {
 
 // Replace the context's orbital set by nbx bands per k-point from device buffers ([nk][nbx][npw_max]
 // complex128; left may be null) with fillings occ ([nk][nbx]).
+// Load nbx orbitals per k-point (per channel and k-point with two spin channels: r and occ channel-major,
+// the first nk nbx fillings for channel 0).
 void load_set(tc_ctx* c, const double* r, const double* l, int nbx, const std::vector<double>& occ) {
   Problem& pb = c->pb;
   pb.nb = nbx;
-  pb.occ = occ;
+  const size_t per = size_t(pb.nk) * nbx;
+  pb.occ.assign(occ.begin(), occ.begin() + per);
+  if (pb.nspin == 2) {
+    pb.occ_dn.assign(occ.begin() + per, occ.begin() + 2 * per);
+    std::fill(pb.loaded_dn.begin(), pb.loaded_dn.end(), 1);
+  }
   std::fill(pb.loaded.begin(), pb.loaded.end(), 1);
   std::fill(pb.left.begin(), pb.left.end(), l ? 1 : 0);
-  const size_t n = size_t(2) * pb.P() * pb.npw_max;
+  const size_t n = size_t(2) * pb.nspin * pb.P() * pb.npw_max;
   c->sh.coef.alloc(n);
   TC_HIP(hipMemcpyAsync(c->sh.coef.p, r, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
   if (l) {
@@ -3732,16 +3819,33 @@ int do_scf(tc_ctx* c, const tc_scf_params& prm, double* ehist, int* niter) {
                 "scf parameters out of range (max_iter >= 1, 0 <= pmax <= 16, etol > 0, 0 < mix <= 1)");
   int st = prepare(c);
   if (st != TC_OK) return st;
-  if (c->pb.nspin == 2) return fail(c, TC_ERR_UNSUPPORTED, "the self-consistent loop is built for unpolarised runs");
   if (c->pb.nsym > 0) return fail(c, TC_ERR_UNSUPPORTED, "the self-consistent loop is built without symmetry");
   Problem& pb = c->pb;
   Shared& sh = c->sh;
   hipStream_t s = c->stream;
   const bool bitc = pb.bitc;
-  const int nk = pb.nk, nb = pb.nb, npm = pb.npw_max, P = pb.P();
+  // two spin channels (Eq. SCF per spin): each (channel, k-point) pair is one subspace block of its own
+  // (nk below counts them), and one application serves the trial vectors of both channels
+  const int ns = pb.nspin;
+  const int nk = ns * pb.nk, nb = pb.nb, npm = pb.npw_max, P = ns * pb.P();
   const int nblk_sub = prm.pmax + 1, M = nblk_sub * nb;
   if (M > 512) return fail(c, TC_ERR_UNSUPPORTED, "subspace larger than 512 vectors per k-point");
-  const std::vector<double> f = pb.occ;        // fillings of the orbitals, [nk][nb]
+  std::vector<double> f = pb.occ;              // fillings of the orbitals, [channel][nk][nb]
+  if (ns == 2) f.insert(f.end(), pb.occ_dn.begin(), pb.occ_dn.end());
+  const int* npwx = sh.npw.p;                  // plane-wave counts and k + G per block
+  const double* kgx = sh.kg.p;
+  if (ns == 2) {
+    const int nk1 = pb.nk;
+    c->dnpw2.alloc(2 * size_t(nk1));
+    c->dkg2.alloc(size_t(2) * nk1 * npm * 3);
+    for (int h = 0; h < 2; ++h) {
+      TC_HIP(hipMemcpyAsync(c->dnpw2.p + h * nk1, sh.npw.p, nk1 * sizeof(int), hipMemcpyDeviceToDevice, s));
+      TC_HIP(hipMemcpyAsync(c->dkg2.p + size_t(h) * nk1 * npm * 3, sh.kg.p, size_t(nk1) * npm * 3 * sizeof(double),
+                            hipMemcpyDeviceToDevice, s));
+    }
+    npwx = c->dnpw2.p;
+    kgx = c->dkg2.p;
+  }
   const size_t blk = size_t(2) * P * npm;      // doubles per block of nb bands on every k-point
   const size_t kb = size_t(2) * nb * npm;      // doubles per k-point within a block
   c->dV.alloc(nblk_sub * blk);
@@ -3777,24 +3881,24 @@ int do_scf(tc_ctx* c, const tc_scf_params& prm, double* ehist, int* niter) {
   for (; it < prm.max_iter; ++it) {
     TC_HIP(hipMemcpyAsync(c->dV.p, cur_r, blk * sizeof(double), hipMemcpyDeviceToDevice, s));
     TC_HIP(hipMemsetAsync(c->dvalid.p, 0, size_t(nk) * M * sizeof(int), s));
-    hipLaunchKernelGGL(k_gram_schmidt, dim3(nk), dim3(256), 0, s, c->dV.p, c->dvalid.p, sh.npw.p, nk, nb, npm, M, 0,
+    hipLaunchKernelGGL(k_gram_schmidt, dim3(nk), dim3(256), 0, s, c->dV.p, c->dvalid.p, npwx, nk, nb, npm, M, 0,
                        nb, atol, rtol);
     for (int p = 0; p < nblk_sub; ++p) {
       if (p > 0) {
-        hipLaunchKernelGGL(k_precond_residual, dim3(P), dim3(256), 0, s, c->dV.p, c->dHV.p, c->deps.p, sh.kg.p,
-                           sh.npw.p, nk, nb, npm, p, atol);
-        hipLaunchKernelGGL(k_gram_schmidt, dim3(nk), dim3(256), 0, s, c->dV.p, c->dvalid.p, sh.npw.p, nk, nb, npm,
+        hipLaunchKernelGGL(k_precond_residual, dim3(P), dim3(256), 0, s, c->dV.p, c->dHV.p, c->deps.p, kgx,
+                           npwx, nk, nb, npm, p, atol);
+        hipLaunchKernelGGL(k_gram_schmidt, dim3(nk), dim3(256), 0, s, c->dV.p, c->dvalid.p, npwx, nk, nb, npm,
                            M, p * nb, (p + 1) * nb, 0.0, rtol);
       }
       st = do_apply_vectors(c, nb, c->dV.p + p * blk, c->dHV.p + p * blk);
       if (st != TC_OK) return st;
-      hipLaunchKernelGGL(k_add_kinetic, dim3(nblk(long(P) * npm)), dim3(256), 0, s, c->dV.p, c->dHV.p, sh.kg.p,
-                         sh.npw.p, nk, nb, npm, p);
+      hipLaunchKernelGGL(k_add_kinetic, dim3(nblk(long(P) * npm)), dim3(256), 0, s, c->dV.p, c->dHV.p, kgx,
+                         npwx, nk, nb, npm, p);
       if (p == 0)
-        hipLaunchKernelGGL(k_rayleigh, dim3(P), dim3(256), 0, s, c->dV.p, c->dHV.p, sh.npw.p, nk, nb, npm,
+        hipLaunchKernelGGL(k_rayleigh, dim3(P), dim3(256), 0, s, c->dV.p, c->dHV.p, npwx, nk, nb, npm,
                            c->deps.p);
     }
-    hipLaunchKernelGGL(k_subspace_matrix, dim3(nk * M * M), dim3(256), 0, s, c->dV.p, c->dHV.p, sh.npw.p, nk, nb,
+    hipLaunchKernelGGL(k_subspace_matrix, dim3(nk * M * M), dim3(256), 0, s, c->dV.p, c->dHV.p, npwx, nk, nb,
                        npm, M, c->dHs.p);
     hipLaunchKernelGGL(k_subspace_eig, dim3((nk + 63) / 64), dim3(64), 0, s, c->dHs.p, c->dvalid.p, nk, nb, M,
                        c->dwork.p, c->dX.p, c->dY.p, c->deval.p, c->dstatus.p, c->dchange.p);
@@ -3813,7 +3917,7 @@ int do_scf(tc_ctx* c, const tc_scf_params& prm, double* ehist, int* niter) {
                        npm, M, new_r);
     if (!bitc) {
       TC_HIP(hipMemsetAsync(c->dvalid.p, 0, size_t(nk) * M * sizeof(int), s));
-      hipLaunchKernelGGL(k_gram_schmidt, dim3(nk), dim3(256), 0, s, new_r, c->dvalid.p, sh.npw.p, nk, nb, npm, M, 0,
+      hipLaunchKernelGGL(k_gram_schmidt, dim3(nk), dim3(256), 0, s, new_r, c->dvalid.p, npwx, nk, nb, npm, M, 0,
                          nb, 0.0, 0.0);
     } else {
       hipLaunchKernelGGL(k_subspace_combine, dim3(nblk(long(P) * npm)), dim3(256), 0, s, c->dV.p, c->dY.p, nk, nb,
@@ -3863,6 +3967,26 @@ int do_scf(tc_ctx* c, const tc_scf_params& prm, double* ehist, int* niter) {
     run_apply(c, nullptr, nullptr);
   }
   if (niter) *niter = it;
+  return TC_OK;
+}
+
+// Orbitals of one spin channel at k-point ik to the host (tc_get_orbitals / tc_get_orbitals_spin).
+int get_orbitals(tc_ctx* c, int spin, int ik, double* right, double* left) {
+  Problem& pb = c->pb;
+  if (ik < 0 || ik >= pb.nk) return fail(c, TC_ERR_ARG, "k-point index out of range");
+  if (spin < 0 || spin >= pb.nspin) return fail(c, TC_ERR_ARG, "spin channel out of range");
+  if (!(spin == 0 ? pb.loaded[ik] : pb.loaded_dn[ik])) return fail(c, TC_ERR_STATE, "orbitals of this k-point are not loaded");
+  if (left && (spin != 0 || !pb.left[ik])) return fail(c, TC_ERR_STATE, "no left orbitals on this k-point");
+  const int nb = pb.nb, npw = pb.npw[ik], npm = pb.npw_max;
+  std::vector<double> buf(size_t(2) * nb * npm);
+  for (int side = 0; side < 2; ++side) {
+    double* dst = side == 0 ? right : left;
+    if (!dst) continue;
+    const double* src = (side == 0 ? c->sh.coef.p : c->sh.coefL.p) + size_t(2) * (size_t(spin) * pb.nk + ik) * nb * npm;
+    TC_HIP(hipMemcpy(buf.data(), src, buf.size() * sizeof(double), hipMemcpyDeviceToHost));
+    for (int b = 0; b < nb; ++b)
+      std::memcpy(dst + size_t(2) * b * npw, &buf[size_t(2) * b * npm], size_t(2) * npw * sizeof(double));
+  }
   return TC_OK;
 }
 
@@ -4153,6 +4277,10 @@ int tc_scf(tc_ctx* c, const tc_scf_params* prm, double* energies, int* iteration
   });
 }
 
+int tc_get_orbitals_spin(tc_ctx* c, int spin, int ik, double* right, double* left) {
+  return guard(c, [&]() -> int { return get_orbitals(c, spin, ik, right, left); });
+}
+
 int tc_get_orbitals(tc_ctx* c, int ik, double* right, double* left) {
   return guard(c, [&]() -> int {
     Problem& pb = c->pb;
@@ -4179,7 +4307,7 @@ int tc_apply(tc_ctx* c, int nvec, const double* in, double* out) {
     if (nvec <= 0) return fail(c, TC_ERR_ARG, "nvec must be positive");
     int st = prepare(c);
     if (st != TC_OK) return st;
-    const size_t n = size_t(2) * c->pb.nk * nvec * c->pb.npw_max;
+    const size_t n = size_t(2) * c->pb.nspin * c->pb.nk * nvec * c->pb.npw_max;
     c->coefT.alloc(n);
     c->outT.alloc(n);
     TC_HIP(hipMemcpy(c->coefT.p, in, n * sizeof(double), hipMemcpyHostToDevice));

@@ -1594,16 +1594,27 @@ template <typename R, int N>
 struct PassOB {
   static constexpr bool SPLIT = !Fz<R, N>::fits(6);   // V21 and V12 in separate LDS rounds
   static constexpr int NPL = SPLIT ? 3 : 6;
-  // register prefetch of the next round where it costs no spills (FP32 up to 32 points)
-  static constexpr bool PF = sizeof(R) == 4 && N <= 32;
+  // register prefetch of the next round where it costs no spills (FP32 up to 16 points); at 24 points
+  // the kernel runs at 3 waves per SIMD without it instead
+  static constexpr bool PF = sizeof(R) == 4 && N <= 16;
+  static constexpr int WAVES = (sizeof(R) == 4 && N == 24) ? 3 : 1;
 };
 
+// Field offsets (in N^3 units) of pair (row t of the batch, partner q): t sT + q sQ for V21 and for V12;
+// sT < 0: the pair-major layout of the pass's own z stages (sT = 4P, sQ = 4).  With the resident store of
+// pass-A z-stage outputs ([pair][5], fields 1..4 as here): V21 of (a, b) is stored pair (t = b, q = a) and
+// V12 is stored pair (t = a, q = b).
 template <typename R, int N>
-__global__ void __launch_bounds__((Fz<R, N>::NTH)) k_fused_OB(const cx<R>* buf21, const cx<R>* buf12,
+__global__ void __launch_bounds__((Fz<R, N>::NTH)) __attribute__((amdgpu_waves_per_eu(PassOB<R, N>::WAVES)))
+k_fused_OB(const cx<R>* buf21, const cx<R>* buf12,
                                                             const cx<R>* psi, const cx<R>* chi, const double* w,
                                                             FusedArgs fa, MeshInfo mi, Recip rc, const double* dfr,
-                                                            cx<R>* h5part, cx<R>* H3part, cx<R>* Hbpart) {
+                                                            cx<R>* h5part, cx<R>* H3part, cx<R>* Hbpart,
+                                                            long sT21 = -1, long sQ21 = 4, long sT12 = -1,
+                                                            long sQ12 = 4) {
   using F = Fz<R, N>;
+  if (sT21 < 0) sT21 = 4L * fa.P;
+  if (sT12 < 0) sT12 = 4L * fa.P;
   constexpr int KP = F::KP, RB = F::RB, PL = F::PLANE;
   constexpr bool SPLIT = PassOB<R, N>::SPLIT, PF = PassOB<R, N>::PF;
   constexpr long NR = long(N) * N * N;
@@ -1623,9 +1634,8 @@ __global__ void __launch_bounds__((Fz<R, N>::NTH)) k_fused_OB(const cx<R>* buf21
   // loaded into registers while this round is transformed; otherwise at the start of each round.
   cx<R> pre[4][KP], pp[2][KP];
   auto fetch = [&](int q, int ch) {
-    const long pair = long(wg.t) * fa.P + q;
-    const cx<R>* s21 = buf21 + pair * 4 * NR + wg.zo;
-    const cx<R>* s12 = buf12 + pair * 4 * NR + wg.zo;
+    const cx<R>* s21 = buf21 + (long(wg.t) * sT21 + long(q) * sQ21) * NR + wg.zo;
+    const cx<R>* s12 = buf12 + (long(wg.t) * sT12 + long(q) * sQ12) * NR + wg.zo;
 #pragma unroll
     for (int i = 0; i < KP; ++i) {
       const long o = RB * N * i;

@@ -64,11 +64,13 @@ def test_every_term_fp64(case):
         assert err < FP64_TOL, (t, err)
 
 
-@pytest.mark.parametrize("batch", [0, 1])
-def test_total_and_energy_fp64(case, batch):
+@pytest.mark.parametrize("batch,store", [(0, True), (1, True), (0, False), (1, False)])
+def test_total_and_energy_fp64(case, batch, store):
+    """With the resident pair store (both occupied-pass convolutions read from pass A's z stage) and
+    without it (the occupied pass transforms conj(chi_a) psi_b and conj(chi_b) psi_a itself)."""
     name, w, per, tot, E = case
-    _say(f"[gpu] bitc {name} fp64 all terms batch={batch}")
-    op = tc.from_workload(w, precision=tc.TC_PREC_FP64, batch=batch)
+    _say(f"[gpu] bitc {name} fp64 all terms batch={batch} pair_store={store}")
+    op = tc.from_workload(w, precision=tc.TC_PREC_FP64, batch=batch, pair_store=store)
     hc = op.apply()
     Eg, _ = op.energy()
     op.close()
@@ -85,7 +87,7 @@ def test_total_and_energy_reduced(case, prec):
         pytest.skip("split-BF16 z stage needs a grid length divisible by 8")
     _say(f"[gpu] bitc {name} {prec} all terms")
     p = tc.TC_PREC_FP32 if prec == "fp32" else tc.TC_PREC_FP32_SPLITBF16
-    op = tc.from_workload(w, precision=p, batch=2)
+    op = tc.from_workload(w, precision=p, batch=2, pair_store=prec == "fp32")
     hc = op.apply()
     Eg, _ = op.energy()
     op.close()

@@ -217,3 +217,30 @@ def test_grid_48_all_terms(prec, tol):
             e = max(np.abs(a - b).max() for a, b in zip(hc, per[t])) / scale
             _say(f"    term {t}: {e:.3e}")
             assert e < FP64_TOL, (t, e)
+
+
+@pytest.fixture(scope="module")
+def fcc_k222_g24_bitc():
+    w = T.fcc_si(kmesh=(2, 2, 2), left_mix=0.1)
+    _say("[oracle] fcc_si_x1_k2x2x2_g24 biorthogonal: all terms (FP64 CPU)")
+    pr = Problem(w)
+    tot = [c.numpy() for c in pr.to_coeff(sum(MULT.get(t, 1) * pr.term(t, 0) for t in ALL))]
+    return w, tot, float(pr.energy())
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_bench_grid_bitc_all_terms(fcc_k222_g24_bitc, prec):
+    """The biorthogonal mode at the bench grid with the resident pair store serving both occupied-pass
+    convolutions, and a partial last batch."""
+    w, tot, E = fcc_k222_g24_bitc
+    P = tc.TC_PREC_FP64 if prec == "fp64" else tc.TC_PREC_FP32
+    _say(f"[gpu] fcc_si k222 24^3 biorthogonal {prec} all terms, batch 5")
+    op = tc.from_workload(w, precision=P, batch=5)
+    hc = op.apply()
+    Eg, _ = op.energy()
+    op.close()
+    scale = max(np.abs(x).max() for x in tot)
+    err = max(np.abs(a - b).max() for a, b in zip(hc, tot)) / scale
+    _say(f"    max element error / max |h c| = {err:.3e}; energy rel {abs(Eg - E) / abs(E):.3e}")
+    assert err < (FP64_TOL if prec == "fp64" else FP32_TOL)
+    assert abs(Eg - E) < (FP64_TOL if prec == "fp64" else 1e-6) * abs(E)

@@ -1,9 +1,11 @@
 """Spin-polarised TC mode of the HIP path through the C ABI: each spin channel has its own orbitals.
 
 Against the FP64 oracle on the same inputs: every term of both spin channels, the totals, the energy
-and its parts, and the orbital energies of both channels (FP64 and FP32).  Independent of the oracle:
-two identical channels reproduce the unpolarised run, and exchanging the channels exchanges the
-outputs and keeps the energy.  The unsupported calls with two channels fail with TC_ERR_UNSUPPORTED.
+and its parts, the orbital energies of both channels (FP64 and FP32), the gradient of each channel's
+coefficients and of A, C (autograd), each channel's operator on trial vectors, and the fixed point of
+the two-channel SCF loop (per-channel plane-wave matrices).  Independent of the oracle: two identical
+channels reproduce the unpolarised run and its SCF iterates, and exchanging the channels exchanges
+the outputs and keeps the energy.  Left orbitals in a polarised channel fail with TC_ERR_UNSUPPORTED.
 """
 import numpy as np
 import pytest
@@ -132,12 +134,6 @@ def test_unsupported_calls_with_two_channels():
     w = T.polarized(T.tiny_fcc(kmesh=(2, 1, 1), grid=8, ecut=2.0, nb=2, a=6.0, occ=[1.0, 0.7]), 9)
     _say("[gpu] polarised unsupported calls")
     op = tc.from_workload(w, precision=tc.TC_PREC_FP64)
-    with pytest.raises(tc.TCError, match="status"):
-        op.apply_vectors([np.zeros((1, n), complex) for n in op.npw])
-    with pytest.raises(tc.TCError, match="status"):
-        op.scf(max_iter=2)
-    with pytest.raises(tc.TCError, match="status"):
-        op.backward()
     with pytest.raises(tc.TCError, match="status"):   # left orbitals in a polarised channel
         op.load_orbitals(0, w.right_dn[0], w.occ_dn[0], left=w.right_dn[0], spin=1)
     op.close()
@@ -156,3 +152,117 @@ def test_unsupported_calls_with_two_channels():
     with pytest.raises(tc.TCError, match="status"):
         op.apply()
     op.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_polarized_gradient_vs_oracle(prec):
+    """2 dE/dc* of each spin channel's own coefficients and dE/dA, dE/dC against the oracle's autograd
+    (one application with the gradient tables, both channels, scale 2 per channel)."""
+    from oracle import grad as OG
+
+    w = T.polarized(T.tiny_fcc(kmesh=(2, 1, 1), grid=8, ecut=2.0, nb=2, a=6.0, occ=[1.0, 0.6]), 41,
+                    occ_dn=[0.9, 0.3])
+    E, gu, gd, gA, gC = OG.energy_and_grad_polarized(w)
+    _say(f"[gpu] polarized backward {prec} vs oracle autograd")
+    op = tc.from_workload(w, precision=tc.TC_PREC_FP64 if prec == "fp64" else tc.TC_PREC_FP32)
+    Eg, _ = op.energy()
+    (hu, hd), dA, dC = op.backward()
+    op.close()
+    tol = 1e-10 if prec == "fp64" else 2e-6
+    scale = max(np.abs(x).max() for x in gu + gd)
+    err = max(np.abs(a - b).max() for a, b in zip(hu + hd, gu + gd)) / scale
+    perr = max(np.abs(dA - gA).max(), np.abs(dC - gC).max()) / max(np.abs(gA).max(), np.abs(gC).max())
+    _say(f"    E {Eg!r} vs {E!r}; grad rel err {err:.3e}; params rel err {perr:.3e}")
+    assert abs(Eg - E) < (1e-10 if prec == "fp64" else 1e-6) * abs(E)
+    assert err < tol
+    assert perr < (1e-10 if prec == "fp64" else 1e-6)
+
+
+def _pol_small():
+    return T.polarized(T.tiny_fcc(kmesh=(2, 1, 1), grid=8, ecut=2.0, nb=2, a=6.0, occ=[1.0, 0.6]), 41,
+                       occ_dn=[0.9, 0.3])
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp32", 2e-6)])
+def test_polarized_trial_vectors_vs_oracle(prec, tol):
+    """tc_apply with two channels: each channel's trial vectors against its own operator.  The oracle adds
+    them to their channel as bands of zero filling (targets of every term, partners of none)."""
+    w = _pol_small()
+    rng = np.random.default_rng(5)
+    nv = 3
+    B = 2 * np.pi * np.linalg.inv(np.asarray(w.lattice)).T
+    env = [np.exp(-0.15 * np.sum(((w.kfrac[k][None, :] + m) @ B) ** 2, 1)) for k, m in enumerate(w.miller)]
+    vecs = [[(rng.standard_normal((nv, m.shape[0])) + 1j * rng.standard_normal((nv, m.shape[0]))) * e
+             for m, e in zip(w.miller, env)] for _ in range(2)]
+    od = w.occ_dn
+    wx = w.replace(right=[np.concatenate([a, v]) for a, v in zip(w.right, vecs[0])],
+                   right_dn=[np.concatenate([a, v]) for a, v in zip(w.right_dn, vecs[1])],
+                   occ=[np.concatenate([o, np.zeros(nv)]) for o in w.occ],
+                   occ_dn=[np.concatenate([o, np.zeros(nv)]) for o in od])
+    pr = Problem(wx)
+    nb = w.right[0].shape[0]
+    ref = []
+    for s in (0, 1):
+        g = sum(MULT.get(t, 1) * pr.term(t, s) for t in ALL_TERMS)
+        ref.append([c.numpy()[nb:] for c in pr.to_coeff(g, s)])
+    _say(f"[gpu] polarized trial vectors {prec} vs oracle")
+    op = tc.from_workload(w, precision=tc.TC_PREC_FP64 if prec == "fp64" else tc.TC_PREC_FP32)
+    op.energy()
+    got = op.apply_vectors(vecs)
+    op.close()
+    scale = max(np.abs(x).max() for r in ref for x in r)
+    err = max(np.abs(a - b).max() for s in (0, 1) for a, b in zip(got[s], ref[s])) / scale
+    _say(f"    max element error / max |h v| = {err:.3e}")
+    assert err < tol
+
+
+def test_polarized_scf_with_equal_channels_follows_the_unpolarized_loop():
+    """Two identical channels are the unpolarised problem: the two-channel block-Davidson loop (one
+    subspace per channel and k-point) takes the same steps and energies."""
+    w = T.tiny_fcc(kmesh=(2, 1, 1), grid=8, ecut=2.0, nb=2, a=6.0, occ=[1.0, 0.7])
+    wp = w.replace(right_dn=[c.copy() for c in w.right], occ_dn=[o.copy() for o in w.occ])
+    _say("[gpu] polarized scf with equal channels vs the unpolarized loop")
+    out = []
+    for ww in (w, wp):
+        op = tc.from_workload(ww, precision=tc.TC_PREC_FP64)
+        hist, n = op.scf(max_iter=5, pmax=2, etol=1e-300, otol=0.0)
+        out.append(np.array(hist[:n]))
+        op.close()
+    _say(f"    energies {out[0]} vs {out[1]}")
+    assert len(out[0]) == len(out[1])
+    np.testing.assert_allclose(out[1], out[0], rtol=1e-10)
+
+
+def test_polarized_scf_fixed_point_vs_oracle():
+    """A spin-polarised loop to convergence; the oracle then builds each channel's matrix of T + h from the
+    final orbitals of both channels: each channel's orbitals span an invariant subspace of its matrix,
+    with its lowest eigenvalues."""
+    from oracle import scf as S
+
+    w = _pol_small()
+    _say("[gpu] polarized scf to convergence; fixed point checked by the oracle per channel")
+    op = tc.from_workload(w, precision=tc.TC_PREC_FP64)
+    hist, n = op.scf(max_iter=1500, pmax=2, etol=1e-13, otol=1e-9)
+    E = op.energy()[0]
+    R = [[op.get_orbitals(k, spin=s) for k in range(w.nk)] for s in (0, 1)]
+    op.close()
+    worst_r = worst_e = 0.0
+    for s in (0, 1):
+        H = S.operator_matrices(w, R[0], spin=s, right_dn=R[1])
+        for k in range(w.nk):
+            Phi = R[s][k].T
+            Hk = H[k]
+            Ek = Phi.conj().T @ Hk @ Phi
+            assert np.abs(Phi.conj().T @ Phi - np.eye(Phi.shape[1])).max() < 1e-10
+            worst_r = max(worst_r, np.abs(Hk @ Phi - Phi @ Ek).max() / np.abs(Hk).max())
+            lam = np.sort(np.linalg.eigvals(Hk).real)
+            mine = np.sort(np.linalg.eigvals(Ek).real)
+            worst_e = max(worst_e, np.abs(mine - lam[: len(mine)]).max())
+    from oracle import grad as OG
+    Eo = OG.energy_polarized(w, up=R[0], dn=R[1])
+    _say(f"    {n} iterations, E = {E!r} (oracle {Eo!r}); invariance residual {worst_r:.2e}; "
+         f"eigenvalue gap {worst_e:.2e}")
+    assert n < 1500
+    assert abs(E - Eo) < 1e-10 * abs(Eo)
+    assert worst_r < 1e-6
+    assert worst_e < 1e-6

@@ -79,3 +79,51 @@ def test_bitc_gradient_reduces_to_tc_when_left_equals_right():
     assert E == pytest.approx(E0, rel=1e-13)
     for a, b, c in zip(gr, gl, g0):
         np.testing.assert_allclose(a + b, c, atol=1e-12 * np.abs(c).max())
+
+
+# ---------------------------------------------------------------- spin-polarised channels
+@pytest.fixture(scope="module")
+def pol_case():
+    w = T.polarized(T.tiny_fcc(kmesh=(2, 1, 1), grid=8, ecut=2.0, nb=2, a=6.0, occ=[1.0, 0.6]), 41,
+                    occ_dn=[0.9, 0.3])
+    return w, OG.energy_and_grad_polarized(w)
+
+
+@pytest.mark.parametrize("side", ["up", "dn"])
+def test_polarized_gradient_matches_central_differences(pol_case, side):
+    w, (E, gu, gd, gA, gC) = pol_case
+    rng = np.random.default_rng(11 if side == "up" else 12)
+    h = 1e-5
+    base = w.right if side == "up" else w.right_dn
+    g = gu if side == "up" else gd
+    for trial in range(2):
+        d = [rng.standard_normal(c.shape) + 1j * rng.standard_normal(c.shape) for c in base]
+        plus = [c + h * x for c, x in zip(base, d)]
+        minus = [c - h * x for c, x in zip(base, d)]
+        if side == "up":
+            fd = (OG.energy_polarized(w, up=plus) - OG.energy_polarized(w, up=minus)) / (2 * h)
+        else:
+            fd = (OG.energy_polarized(w, dn=plus) - OG.energy_polarized(w, dn=minus)) / (2 * h)
+        an = sum(np.sum((np.conj(a) * x).real) for a, x in zip(g, d))
+        assert an == pytest.approx(fd, rel=1e-6, abs=1e-9)
+    Ap = np.array(w.A, dtype=float)
+    Am = Ap.copy()
+    Ap[0] += h
+    Am[0] -= h
+    fdA = (OG.energy_polarized(w, A=Ap, C=np.array(w.C)) - OG.energy_polarized(w, A=Am, C=np.array(w.C))) / (2 * h)
+    assert gA[0] == pytest.approx(fdA, rel=1e-6, abs=1e-9)
+
+
+def test_equal_channels_share_the_unpolarized_gradient():
+    """Two identical channels: each channel's gradient is half of the unpolarised one (which differentiates
+    the coefficients that both spins share), and dA, dC are the same."""
+    w = T.tiny_fcc(kmesh=(2, 1, 1), grid=8, ecut=2.0, nb=2, a=6.0, occ=[1.0, 0.6])
+    E0, g0, gA0, gC0 = OG.energy_and_grad(w)
+    wp = w.replace(right_dn=[c.copy() for c in w.right], occ_dn=[o.copy() for o in w.occ])
+    E, gu, gd, gA, gC = OG.energy_and_grad_polarized(wp)
+    assert E == pytest.approx(E0, rel=1e-13)
+    for a, b, c in zip(gu, gd, g0):
+        np.testing.assert_allclose(a + b, c, rtol=0, atol=1e-12 * np.abs(c).max())
+        np.testing.assert_allclose(a, b, rtol=0, atol=1e-12 * np.abs(c).max())
+    np.testing.assert_allclose(gA, gA0, rtol=1e-12)
+    np.testing.assert_allclose(gC, gC0, rtol=1e-12)

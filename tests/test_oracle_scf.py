@@ -55,3 +55,15 @@ def test_operator_matrix_diagonal_is_the_closed_form(heg2, reading):
     assert np.abs(np.diag(H) - ref).max() < 1e-12 * np.abs(ref).max()
     # the closed forms differ between the plane waves, so a wrong scale of any entry shows
     assert np.ptp(ref.real) > 1e-2 * np.abs(ref).max()
+
+
+def test_polarized_operator_matrices_with_equal_channels():
+    """The per-channel plane-wave matrices of a polarised workload with two identical channels are the
+    unpolarised matrix, for both channels."""
+    w = T.tiny_fcc(kmesh=(2, 1, 1), grid=6, ecut=1.5, nb=1, a=6.0)
+    wp = w.replace(right_dn=[c.copy() for c in w.right], occ_dn=[o.copy() for o in w.occ])
+    H0 = S.operator_matrices(w, w.right)
+    for s in (0, 1):
+        Hs = S.operator_matrices(wp, wp.right, spin=s)
+        for a, b in zip(Hs, H0):
+            assert np.abs(a - b).max() < 1e-12 * np.abs(b).max()
