@@ -31,22 +31,6 @@ __global__ void k_band_dh4(const cx<R>* psiT, const double* a, const double* V, 
   }
 }
 
-__device__ __forceinline__ void block_sum2(double& x, double& y) {
-  __shared__ double rx[256], ry[256];
-  rx[threadIdx.x] = x;
-  ry[threadIdx.x] = y;
-  __syncthreads();
-  for (int h = blockDim.x / 2; h > 0; h >>= 1) {
-    if (int(threadIdx.x) < h) {
-      rx[threadIdx.x] += rx[threadIdx.x + h];
-      ry[threadIdx.x] += ry[threadIdx.x + h];
-    }
-    __syncthreads();
-  }
-  x = rx[0];
-  y = ry[0];
-}
-
 // Band-pair grid means (one work-group of 256 per output):
 //   out[((j) nb + mu) nc + c] = (1/N^3) sum_r conj(A_(b nb + mu), c) B_(j), c [F_c]
 // for targets j in [j0, j0 + nj), b = j / nb; A rows b nb + mu with stride sA per row and sAc per
@@ -74,7 +58,7 @@ __global__ void __launch_bounds__(256) k_band_dot(const cx<TA>* A, long sA, long
     sr += ar * br - ai * bi;
     si += ar * bi + ai * br;
   }
-  block_sum2(sr, si);
+  wg_sum2(sr, si);
   if (threadIdx.x == 0) {
     const long idx = (long(o / (nc * nb)) + j0) * nb * nc + long(mu) * nc + c;
     out[2 * idx] = sr / double(NR);

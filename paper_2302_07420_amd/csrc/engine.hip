@@ -383,20 +383,10 @@ __global__ void k_overlap(const double* a, int na, const double* b, int nbb, con
     sr += x[2 * g] * y[2 * g] + x[2 * g + 1] * y[2 * g + 1];
     si += x[2 * g] * y[2 * g + 1] - x[2 * g + 1] * y[2 * g];
   }
-  __shared__ double rr[256], ri[256];
-  rr[threadIdx.x] = sr;
-  ri[threadIdx.x] = si;
-  __syncthreads();
-  for (int h = blockDim.x / 2; h > 0; h >>= 1) {
-    if (int(threadIdx.x) < h) {
-      rr[threadIdx.x] += rr[threadIdx.x + h];
-      ri[threadIdx.x] += ri[threadIdx.x + h];
-    }
-    __syncthreads();
-  }
+  wg_sum2(sr, si);
   if (threadIdx.x == 0) {
-    S[2 * id] = rr[0];
-    S[2 * id + 1] = ri[0];
+    S[2 * id] = sr;
+    S[2 * id + 1] = si;
   }
 }
 
@@ -412,14 +402,8 @@ __global__ void k_kinetic(const double* cl, const double* c, const double* kg, c
     const double* y = c + 2 * (long(p) * npw_max + g);
     s += e * (x[0] * y[0] + x[1] * y[1]);
   }
-  __shared__ double red[256];
-  red[threadIdx.x] = s;
-  __syncthreads();
-  for (int h = blockDim.x / 2; h > 0; h >>= 1) {
-    if (int(threadIdx.x) < h) red[threadIdx.x] += red[threadIdx.x + h];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) t[p] = red[0];
+  s = wg_sum(s);
+  if (threadIdx.x == 0) t[p] = s;
 }
 
 // Orbital gradient from an application: grad_p = scale w_p [(h' c_p)(G) + |k+G|^2/2 c_p(G)], w_p = f_p / N_k.
@@ -458,20 +442,10 @@ __global__ void __launch_bounds__(256) k_orbital_eps(const double* cl, const dou
     sr += cl[o] * yr + cl[o + 1] * yi;
     si += cl[o] * yi - cl[o + 1] * yr;
   }
-  __shared__ double rr[256], ri[256];
-  rr[threadIdx.x] = sr;
-  ri[threadIdx.x] = si;
-  __syncthreads();
-  for (int h = blockDim.x / 2; h > 0; h >>= 1) {
-    if (int(threadIdx.x) < h) {
-      rr[threadIdx.x] += rr[threadIdx.x + h];
-      ri[threadIdx.x] += ri[threadIdx.x + h];
-    }
-    __syncthreads();
-  }
+  wg_sum2(sr, si);
   if (threadIdx.x == 0) {
-    eps[2 * j] = rr[0];
-    eps[2 * j + 1] = ri[0];
+    eps[2 * j] = sr;
+    eps[2 * j + 1] = si;
   }
 }
 
@@ -485,14 +459,8 @@ __global__ void __launch_bounds__(256) k_bo_normalize(double* c, int npw, int np
   double* x = c + 2 * long(blockIdx.x) * npw_max;
   double s = 0;
   for (int g = threadIdx.x; g < npw; g += blockDim.x) s += x[2 * g] * x[2 * g] + x[2 * g + 1] * x[2 * g + 1];
-  __shared__ double red[256];
-  red[threadIdx.x] = s;
-  __syncthreads();
-  for (int h = blockDim.x / 2; h > 0; h >>= 1) {
-    if (int(threadIdx.x) < h) red[threadIdx.x] += red[threadIdx.x + h];
-    __syncthreads();
-  }
-  const double nrm = sqrt(red[0]);
+  s = wg_sum(s);
+  const double nrm = sqrt(s);
   if (!(nrm > 0.0)) {
     if (threadIdx.x == 0) bad[0] = 1;
     return;
@@ -709,20 +677,10 @@ __global__ void k_corr_add(const double* c, const double* dhc2, const double* dh
       out[o + 1] += dhc2[o + 1] + dhc3[o + 1];
     }
   }
-  __shared__ double r2[256], r3[256];
-  r2[threadIdx.x] = e2;
-  r3[threadIdx.x] = e3;
-  __syncthreads();
-  for (int h = blockDim.x / 2; h > 0; h >>= 1) {
-    if (int(threadIdx.x) < h) {
-      r2[threadIdx.x] += r2[threadIdx.x + h];
-      r3[threadIdx.x] += r3[threadIdx.x + h];
-    }
-    __syncthreads();
-  }
+  wg_sum2(e2, e3);
   if (threadIdx.x == 0) {
-    ecorr[2 * j] = r2[0];
-    ecorr[2 * j + 1] = r3[0];
+    ecorr[2 * j] = e2;
+    ecorr[2 * j + 1] = e3;
   }
 }
 

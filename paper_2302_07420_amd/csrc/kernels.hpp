@@ -12,6 +12,7 @@
 // physical convolution sum_G K(Delta+G) FT[source_phys](G) e^{iG.r}.
 #pragma once
 #include "fft_reg.hpp"
+#include "reduce.hpp"
 #include <hip/hip_bf16.h>
 
 namespace tcmi {
@@ -403,7 +404,10 @@ struct Fz {
   static constexpr int kFitPlanes = kLdsMax / (PLANE * int(sizeof(cx<R>)));
   static constexpr int GRP = kFitPlanes < RB ? kFitPlanes : RB;   // one-plane-per-partner rounds
   static constexpr bool COMB = N == 48;                    // comb transforms, outputs in sigma order
-  static constexpr bool PREFETCH = N < 48;                 // next partner's planes loaded into registers
+  // the next partner's planes are loaded into registers while this partner's are transformed; at 48
+  // points the register budget allows it in FP32 only, and k_fused_A measured faster without it there
+  static constexpr bool PREFETCH = N < 48 || sizeof(R) == 4;
+  static constexpr bool PREFETCH_A = N < 48;
 };
 
 // Position of index k after the in-place comb transform of a 48-point axis (planes_comb48): the
@@ -1267,7 +1271,7 @@ k_fused_A(const cx<R>* buf5, const cx<R>* psi, const cx<R>* Dl, const cx<R>* Hl,
   using F = Fz<R, N>;
   constexpr int KP = F::KP, RB = F::RB, PL = F::PLANE;
   constexpr bool SPLIT = PassA<R, N>::SPLIT;
-  constexpr bool PF = !SPLIT && F::PREFETCH;
+  constexpr bool PF = !SPLIT && F::PREFETCH_A;
   constexpr long NR = long(N) * N * N;
   __shared__ cx<R> sm[PassA<R, N>::NPL * PL];
   const PlaneWG<R, N> wg(fa);
@@ -1878,8 +1882,8 @@ __global__ void k_local(const cx<R>* psi, const cx<R>* D, const cx<R>* loc, cons
   g[long(t) * NR + r] = mk<R>(R(gx), R(gy));
 }
 
-// Energy partials: e[j*kAccSlots + slot] = Re sum_r conj(chi_j) acc_slot,t / N^3 (deterministic tree, one block
-// per (t, slot); chi = psi in TC mode)
+// Energy partials: e[j*kAccSlots + slot] = Re sum_r conj(chi_j) acc_slot,t / N^3 (deterministic work-group
+// sum, one block per (t, slot); chi = psi in TC mode)
 template <typename R, int N>
 __global__ void __launch_bounds__(256) k_epart(const cx<R>* chi, const cx<double>* acc, int t0, int T, double* e) {
   constexpr long NR = long(N) * N * N;
@@ -1888,14 +1892,8 @@ __global__ void __launch_bounds__(256) k_epart(const cx<R>* chi, const cx<double
   const cx<double>* a = acc + (long(slot) * T + t) * NR;
   double s = 0;
   for (long r = threadIdx.x; r < NR; r += blockDim.x) s += double(p[r].x) * a[r].x + double(p[r].y) * a[r].y;
-  __shared__ double red[256];
-  red[threadIdx.x] = s;
-  __syncthreads();
-  for (int h = blockDim.x / 2; h > 0; h >>= 1) {
-    if (int(threadIdx.x) < h) red[threadIdx.x] += red[threadIdx.x + h];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) e[long(t0 + t) * kAccSlots + slot] = red[0] / double(NR);
+  s = wg_sum(s);
+  if (threadIdx.x == 0) e[long(t0 + t) * kAccSlots + slot] = s / double(NR);
 }
 
 // h6 = sum_a w_a h5[a];  M_c = sum_a w_a conj(H3c[a]_c) psi_a, H3c = conj(H3b) (Alg. 3b2 source;

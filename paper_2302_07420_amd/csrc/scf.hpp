@@ -4,27 +4,11 @@
 // k-point k, band i; column j = p nb + i of the subspace of k-point k.  The same layout holds h V.
 #pragma once
 #include "eig_small.hpp"
+#include "reduce.hpp"
 
 namespace tcmi {
 
 __device__ __forceinline__ long sub_row(int p, int k, int i, int nk, int nb) { return (long(p) * nk + k) * nb + i; }
-
-// block sum of two doubles over 256 threads (every thread gets the result)
-__device__ __forceinline__ void block_sum2(double& a, double& b, double* ra, double* rb) {
-  ra[threadIdx.x] = a;
-  rb[threadIdx.x] = b;
-  __syncthreads();
-  for (int h = blockDim.x / 2; h > 0; h >>= 1) {
-    if (int(threadIdx.x) < h) {
-      ra[threadIdx.x] += ra[threadIdx.x + h];
-      rb[threadIdx.x] += rb[threadIdx.x + h];
-    }
-    __syncthreads();
-  }
-  a = ra[0];
-  b = rb[0];
-  __syncthreads();
-}
 
 // Gram-Schmidt of columns j0..j1-1 of each k-point's subspace against all earlier valid columns (and
 // each other, in order), classical with one re-orthogonalisation pass.  A column whose norm is below atol
@@ -34,13 +18,12 @@ __global__ void __launch_bounds__(256) k_gram_schmidt(double* V, int* valid, con
                                                      int npw_max, int mcols, int j0, int j1, double atol,
                                                      double rtol) {
   const int k = blockIdx.x;
-  __shared__ double ra[256], rb[256];
   const int n = npw[k];
   for (int j = j0; j < j1; ++j) {
     double* vj = V + 2 * sub_row(j / nb, k, j % nb, nk, nb) * npw_max;
     double n0r = 0, n0i = 0;
     for (int g = threadIdx.x; g < n; g += blockDim.x) n0r += vj[2 * g] * vj[2 * g] + vj[2 * g + 1] * vj[2 * g + 1];
-    block_sum2(n0r, n0i, ra, rb);
+    wg_sum2(n0r, n0i);
     const double norm0 = sqrt(n0r);
     for (int pass = 0; pass < 2; ++pass)
       for (int i = 0; i < j; ++i) {
@@ -51,7 +34,7 @@ __global__ void __launch_bounds__(256) k_gram_schmidt(double* V, int* valid, con
           cr += vi[2 * g] * vj[2 * g] + vi[2 * g + 1] * vj[2 * g + 1];
           ci += vi[2 * g] * vj[2 * g + 1] - vi[2 * g + 1] * vj[2 * g];
         }
-        block_sum2(cr, ci, ra, rb);
+        wg_sum2(cr, ci);
         for (int g = threadIdx.x; g < n; g += blockDim.x) {
           const double xr = vi[2 * g], xi = vi[2 * g + 1];
           vj[2 * g] -= cr * xr - ci * xi;
@@ -61,7 +44,7 @@ __global__ void __launch_bounds__(256) k_gram_schmidt(double* V, int* valid, con
       }
     double nr = 0, ni = 0;
     for (int g = threadIdx.x; g < n; g += blockDim.x) nr += vj[2 * g] * vj[2 * g] + vj[2 * g + 1] * vj[2 * g + 1];
-    block_sum2(nr, ni, ra, rb);
+    wg_sum2(nr, ni);
     const double nrm = sqrt(nr);
     const bool ok = norm0 >= atol && nrm > rtol * norm0 && nrm > 1e-300;
     const double sc = ok ? 1.0 / nrm : 0.0;
@@ -93,7 +76,6 @@ __global__ void k_add_kinetic(const double* V, double* HV, const double* kg, con
 __global__ void __launch_bounds__(256) k_rayleigh(const double* V, const double* HV, const int* npw, int nk, int nb,
                                                  int npw_max, double* eps) {
   const int k = blockIdx.x / nb, i = blockIdx.x % nb;
-  __shared__ double ra[256], rb[256];
   const double* v = V + 2 * sub_row(0, k, i, nk, nb) * npw_max;
   const double* h = HV + 2 * sub_row(0, k, i, nk, nb) * npw_max;
   double sr = 0, si = 0;
@@ -101,7 +83,7 @@ __global__ void __launch_bounds__(256) k_rayleigh(const double* V, const double*
     sr += v[2 * g] * h[2 * g] + v[2 * g + 1] * h[2 * g + 1];
     si += v[2 * g] * h[2 * g + 1] - v[2 * g + 1] * h[2 * g];
   }
-  block_sum2(sr, si, ra, rb);
+  wg_sum2(sr, si);
   if (threadIdx.x == 0) {
     eps[2 * (k * nb + i)] = sr;
     eps[2 * (k * nb + i) + 1] = si;
@@ -117,7 +99,6 @@ __global__ void __launch_bounds__(256) k_precond_residual(double* V, const doubl
                                                          const double* kg, const int* npw, int nk, int nb,
                                                          int npw_max, int p, double atol) {
   const int k = blockIdx.x / nb, i = blockIdx.x % nb;
-  __shared__ double ra[256], rb[256];
   const double* v = V + 2 * sub_row(p - 1, k, i, nk, nb) * npw_max;
   const double* h = HV + 2 * sub_row(p - 1, k, i, nk, nb) * npw_max;
   double* out = V + 2 * sub_row(p, k, i, nk, nb) * npw_max;
@@ -131,7 +112,7 @@ __global__ void __launch_bounds__(256) k_precond_residual(double* V, const doubl
     const double ri = h[2 * g + 1] - (er * v[2 * g + 1] + ei * v[2 * g]);
     rn += rr * rr + ri * ri;
   }
-  block_sum2(t, rn, ra, rb);
+  wg_sum2(t, rn);
   const bool keep = sqrt(rn) >= atol;
   for (int g = threadIdx.x; g < npw_max; g += blockDim.x) {
     double rr = 0, ri = 0;
@@ -153,7 +134,6 @@ __global__ void __launch_bounds__(256) k_subspace_matrix(const double* V, const 
                                                         int nb, int npw_max, int mcols, double* Hs) {
   const int id = blockIdx.x;
   const int k = id / (mcols * mcols), a = (id / mcols) % mcols, b = id % mcols;
-  __shared__ double ra[256], rb[256];
   const double* x = V + 2 * sub_row(a / nb, k, a % nb, nk, nb) * npw_max;
   const double* y = HV + 2 * sub_row(b / nb, k, b % nb, nk, nb) * npw_max;
   double sr = 0, si = 0;
@@ -161,7 +141,7 @@ __global__ void __launch_bounds__(256) k_subspace_matrix(const double* V, const 
     sr += x[2 * g] * y[2 * g] + x[2 * g + 1] * y[2 * g + 1];
     si += x[2 * g] * y[2 * g + 1] - x[2 * g + 1] * y[2 * g];
   }
-  block_sum2(sr, si, ra, rb);
+  wg_sum2(sr, si);
   if (threadIdx.x == 0) {
     Hs[2 * id] = sr;
     Hs[2 * id + 1] = si;
