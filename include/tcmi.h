@@ -164,9 +164,8 @@ int tc_set_options(tc_ctx* ctx, int precision, double alpha, int div_correction,
  *   partial pivoting) and the left set becomes conj(S^-1) chi.  TC_ERR_ARG if a
  *   right orbital is zero or S is singular (a pivot not above 1e-13 max|S_ij|); the
  *   k-point is then left unloaded.  Either every k-point or none must have left
- *   orbitals when the operator is applied (else TC_ERR_STATE).  The energy
- *   gradient (tc_energy_backward*) is built for TC mode only: TC_ERR_UNSUPPORTED in
- *   the biorthogonal mode. */
+ *   orbitals when the operator is applied (else TC_ERR_STATE).  The gradients of
+ *   the biorthogonal mode are those of tc_energy_backward_lr. */
 int tc_load_orbitals(tc_ctx* ctx, int ik, int nband, const double* right, const double* left,
                      const double* occ);
 
@@ -175,14 +174,16 @@ int tc_load_orbitals_dev(tc_ctx* ctx, int ik, int nband, const void* right_dev, 
 
 /* Number of spin channels (Sec. 2.1 and Eq. SCF: one orbital set per spin; Sec. 2.6 sums every
  * Hartree-type field over both spins with the Jastrow channel u^{s s'} of the pair).  nspin = 1
- * (default): both channels hold the orbitals of tc_load_orbitals.  nspin = 2: spin-polarised TC mode,
- * the spin-down set is loaded with tc_load_orbitals_spin(ctx, 1, ...), the spin-up set with
+ * (default): both channels hold the orbitals of tc_load_orbitals.  nspin = 2: spin-polarised, in TC mode or
+ * (left orbitals in both channels) the biorthogonal mode; the spin-down set is loaded with
+ * tc_load_orbitals_spin(ctx, 1, ...), the spin-up set with
  * tc_load_orbitals or spin 0.  Both channels have the same nband; exchange-type terms pair orbitals of
  * one spin, the parallel channel serves the own spin's density and partners and the antiparallel channel
  * the other spin's.  Outputs become spin-major: tc_apply_all* writes [2][nk][nband][npw_max] and
  * tc_orbital_energies [2][nk][nband] complex128; tc_energy sums both channels.  Call after the k-mesh;
- * it discards every loaded orbital.  Built for tc_apply_all*, tc_energy and tc_orbital_energies;
- * tc_apply*, tc_scf and tc_energy_backward* return TC_ERR_UNSUPPORTED with two channels.
+ * it discards every loaded orbital.  Every call of the application, the energy, the trial vectors
+ * (tc_apply*), the SCF loop and the gradients takes both channels; symmetry and band k-points are built
+ * for one channel.
  * TC_ERR_ARG unless nspin is 1 or 2; TC_ERR_STATE before the k-mesh. */
 int tc_set_nspin(tc_ctx* ctx, int nspin);
 
@@ -236,9 +237,10 @@ int tc_apply_band(tc_ctx* ctx, double* out, double* eps);
 int tc_set_symmetry(tc_ctx* ctx, int nsym, const int32_t* rot, const double* tau);
 
 /* tc_load_orbitals for spin channel `spin` (0 = up, the set of tc_load_orbitals; 1 = down, needs
- * tc_set_nspin(ctx, 2)).  TC mode only: left must be NULL (TC_ERR_UNSUPPORTED otherwise).  occ are the
- * channel's own fillings in [0, 1].  TC_ERR_STATE for spin 1 with one channel; TC_ERR_ARG for another
- * spin. */
+ * tc_set_nspin(ctx, 2)).  left != NULL: the channel's left orbitals, biorthonormalised with its right ones
+ * as in tc_load_orbitals; left orbitals must be loaded in both channels on every k-point or nowhere (else
+ * TC_ERR_STATE at application).  occ are the channel's own fillings in [0, 1].  TC_ERR_STATE for spin 1
+ * with one channel; TC_ERR_ARG for another spin. */
 int tc_load_orbitals_spin(tc_ctx* ctx, int spin, int ik, int nband, const double* right, const double* left,
                           const double* occ);
 
@@ -320,7 +322,7 @@ int tc_scf(tc_ctx* ctx, const tc_scf_params* prm, double* energies, int* iterati
  * NULL) and, in the biorthogonal mode, left (NULL, or TC_ERR_STATE without left orbitals). */
 int tc_get_orbitals(tc_ctx* ctx, int ik, double* right, double* left);
 
-/* The same for spin channel `spin` (0 or 1 with tc_set_nspin(ctx, 2); left only for channel 0).
+/* The same for spin channel `spin` (0 or 1 with tc_set_nspin(ctx, 2)).
  * TC_ERR_ARG for a channel out of range. */
 int tc_get_orbitals_spin(tc_ctx* ctx, int spin, int ik, double* right, double* left);
 
@@ -366,7 +368,8 @@ int tc_energy_backward_dev(tc_ctx* ctx, void* grad_dev, double dA[2], double dC[
  *      grad_right = 2 dE/dphi* = 2 w (T + h^dagger) chi (the left operator of Eq. BITCSCFconj:
  *        chi and phi exchanged and v2 replaced by its adjoint, whose grad-u . grad terms change
  *        sign and whose scalar kernel becomes 4 pi/Q^2 - lap u~ - (grad u)^2~),
- *    w = f / N_k, one application each.
+ *    w = f / N_k, one application each.  With two spin channels (spin-major [2][nk][nband][npw_max])
+ *    each channel's gradients are those of its own pair: w (T + h) phi and w (T + h^dagger) chi.
  * Term-mask conditions and errors as tc_energy_backward. */
 int tc_energy_backward_lr(tc_ctx* ctx, double* grad_right, double* grad_left, double dA[2], double dC[2]);
 

@@ -126,7 +126,7 @@ class Problem:
     """
 
     def __init__(self, w, A=None, C=None, coeff=None, left=None, div_correction=True,
-                 alpha=None, biorthogonalize=True, reading="printed", coeff_dn=None):
+                 alpha=None, biorthogonalize=True, reading="printed", coeff_dn=None, left_dn=None):
         self.w = w
         self.lattice = np.asarray(w.lattice, dtype=np.float64)
         self.omega = abs(float(np.linalg.det(self.lattice)))
@@ -182,7 +182,10 @@ class Problem:
         self.polarized = getattr(w, "right_dn", None) is not None
         if self.polarized:
             crd = [torch.as_tensor(c, dtype=CD) for c in w.right_dn] if coeff_dn is None else list(coeff_dn)
-            cld = None if w.left_dn is None else [torch.as_tensor(c, dtype=CD) for c in w.left_dn]
+            if left_dn is not None:
+                cld = list(left_dn)
+            else:
+                cld = None if w.left_dn is None else [torch.as_tensor(c, dtype=CD) for c in w.left_dn]
             if cld is not None and biorthogonalize:
                 crd, cld = biorthogonalize_coeffs(crd, cld)
             occd = [torch.as_tensor(o, dtype=RD) for o in (w.occ_dn if w.occ_dn is not None else w.occ)]

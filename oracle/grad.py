@@ -16,7 +16,8 @@ as given (biorthonormalised once beforehand, not differentiated through).
 
 Spin-polarised input (energy_and_grad_polarized, TC mode): one orbital set per spin channel, so one
 gradient 2 dE/dc* per channel.  With two equal channels they add up to the unpolarised gradient, whose
-coefficients both channels share.
+coefficients both channels share.  energy_and_grad_bitc_polarized: the biorthogonal mode with one
+right/left pair per channel, each taken as given.
 """
 from __future__ import annotations
 
@@ -93,3 +94,28 @@ def energy_polarized(w, up=None, dn=None, A=None, C=None, terms=ALL_TERMS, div_c
                      coeff_dn=None if dn is None else [torch.as_tensor(c, dtype=CD) for c in dn],
                      div_correction=div_correction)
         return float(pr.energy(terms=terms))
+
+
+def bitc_pair_polarized(w):
+    """Both channels' right/left pairs after the biorthonormalisation of Sec. 2.3 (numpy arrays):
+    (right_up, left_up, right_dn, left_dn)."""
+    ru, lu = bitc_pair(w)
+    rd, ld = biorthogonalize_coeffs([torch.as_tensor(c, dtype=CD) for c in w.right_dn],
+                                    [torch.as_tensor(c, dtype=CD) for c in w.left_dn])
+    return ru, lu, [c.numpy() for c in rd], [c.numpy() for c in ld]
+
+
+def energy_and_grad_bitc_polarized(w, ru, lu, rd, ld, terms=ALL_TERMS, div_correction=True, reading="printed"):
+    """(E, grad_right_up, grad_left_up, grad_right_dn, grad_left_dn, dA, dC) of the spin-polarised
+    biorthogonal-mode energy at the given pairs."""
+    sets = [[torch.as_tensor(c, dtype=CD).clone().requires_grad_(True) for c in x] for x in (ru, lu, rd, ld)]
+    A = torch.as_tensor(w.A, dtype=RD).clone().requires_grad_(True)
+    C = torch.as_tensor(w.C, dtype=RD).clone().requires_grad_(True)
+    pr = Problem(w, A=A, C=C, coeff=sets[0], left=sets[1], coeff_dn=sets[2], left_dn=sets[3],
+                 div_correction=div_correction, biorthogonalize=False, reading=reading)
+    E = pr.energy(terms=terms)
+    flat = [x for st in sets for x in st]
+    g = torch.autograd.grad(E, flat + [A, C])
+    nk = len(ru)
+    out = [[x.numpy() for x in g[i * nk:(i + 1) * nk]] for i in range(4)]
+    return (float(E.detach()), *out, g[-2].numpy(), g[-1].numpy())

@@ -380,18 +380,23 @@ class TCOperator:
 
     def backward_lr(self, want_right=True, want_left=True, want_params=True):
         """(grad_right, grad_left, dA, dC); biorthogonal mode: the two partial gradients (TC mode: the
-        gradient as grad_right and want_left must be False)."""
-        nk = len(self.npw)
-        gr = np.zeros((nk, self.nband, self.npw_max), dtype=np.complex128) if want_right else None
-        gl = np.zeros_like(gr if gr is not None else np.zeros((nk, self.nband, self.npw_max), complex)) \
-            if want_left else None
+        gradient as grad_right and want_left must be False).  With two spin channels each gradient is
+        [per k of spin 0, per k of spin 1]."""
+        nk, ns = len(self.npw), self.nspin
+        gr = np.zeros((ns * nk, self.nband, self.npw_max), dtype=np.complex128) if want_right else None
+        gl = np.zeros((ns * nk, self.nband, self.npw_max), dtype=np.complex128) if want_left else None
         dA = np.zeros(2) if want_params else None
         dC = np.zeros(2) if want_params else None
         self._check(self._L.tc_energy_backward_lr(self._h, None if gr is None else _dp(gr.view(np.float64)),
                                                   None if gl is None else _dp(gl.view(np.float64)),
                                                   None if dA is None else _dp(dA), None if dC is None else _dp(dC)),
                     "tc_energy_backward_lr")
-        cut = lambda g: None if g is None else [g[k, :, : self.npw[k]].copy() for k in range(nk)]
+        def cut(g):
+            if g is None:
+                return None
+            per = [[g[sp * nk + k, :, : self.npw[k]].copy() for k in range(nk)] for sp in range(ns)]
+            return per[0] if ns == 1 else per
+
         return cut(gr), cut(gl), dA, dC
 
     def backward_dev(self, grad_ptr: Optional[int], want_params=True):
@@ -456,13 +461,14 @@ def from_workload(w, precision=TC_PREC_FP64, terms=TERM_ALL, div_correction=True
     cs = w.right if coeff is None else coeff
     ls = w.left if left is None else left
     dn = getattr(w, "right_dn", None)
-    if dn is not None:   # spin-polarised workload (TC mode)
+    ldn = getattr(w, "left_dn", None)
+    if dn is not None:   # spin-polarised workload (left orbitals of the down channel: biorthogonal mode)
         op.set_nspin(2)
     for ik in range(len(w.miller)):
         op.load_orbitals(ik, cs[ik], w.occ[ik], None if ls is None else ls[ik])
         if dn is not None:
             occd = w.occ_dn if w.occ_dn is not None else w.occ
-            op.load_orbitals(ik, dn[ik], occd[ik], spin=1)
+            op.load_orbitals(ik, dn[ik], occd[ik], None if ldn is None else ldn[ik], spin=1)
     if getattr(w, "band_k", None) is not None:
         op.set_band(w.band_k, w.band_miller, w.band_right, w.band_occ)
     return op

@@ -173,6 +173,7 @@ struct Problem {
   int nspin = 1;                          // 2: spin-polarised, the down channel's own orbitals
   std::vector<double> occ_dn;             // [nk][nb] fillings of the down channel (nspin = 2)
   std::vector<char> loaded_dn;            // per k (nspin = 2)
+  std::vector<char> left_dn;              // per k: the down channel loaded with left orbitals
   double delta_gb = 0, sigma_aux = 0;
   int batch = 0;                          // targets per batch (0 = automatic)
   size_t mem_budget = 0;                  // bytes for the pair store and pair buffers (0: from the device)
@@ -926,6 +927,10 @@ struct EngineT : Engine {
   DBuf<cx<R>> psi1, D1, Dl1, Hl1, H3a4_1, nJ1, loc1, wk2;
   DBuf<R> h5_1, h5a0, h5a1;
   DBuf<cx<double>> psi64_1, v64p;
+  // spin-polarised biorthogonal mode: the down channel's left fields and conj(H3b), the complex h5 of each
+  // channel (the up channel's parallel part is h5c)
+  DBuf<cx<R>> chi1, H3bc_1, h5c_1, h5ca0, h5ca1;
+  DBuf<cx<double>> chi64_1;
   int nspin_alloc = 1;
   // target set of tc_apply (trial vectors)
   DBuf<cx<R>> psiT, DT;              // [NT][NR], [3][NT][NR]
@@ -1274,6 +1279,15 @@ struct EngineT : Engine {
       h5part.alloc(size_t(2) * S * T * NR);
       psi64_1.alloc(size_t(P) * NR);
       v64p.alloc(10 * NR);
+      if (pb.bitc) {
+        chi1.alloc(size_t(P) * NR);
+        H3bc_1.alloc(size_t(3) * P * NR);
+        h5c_1.alloc(size_t(P) * NR);
+        h5ca0.alloc(size_t(P) * NR);
+        h5ca1.alloc(size_t(P) * NR);
+        h5cpart.alloc(size_t(2) * S * T * NR);
+        chi64_1.alloc(size_t(P) * NR);
+      }
     }
     if (t_arena) return;   // the buffers of the no-allocation call are unbound when it ends
     P_alloc = P;
@@ -2017,7 +2031,13 @@ struct EngineT : Engine {
     const int nbt = ts ? ts->nvec : nb;
     const int NTG = pb.nk * nbt;
     const size_t tcofs = size_t(2) * NTG * npm;   // doubles per channel of the trial vectors
-    const Masks m = make_masks(pb.mask);
+    Masks m = make_masks(pb.mask);
+    if (pb.negate_b) {   // v2 -> v2^dagger (the left gradient of the biorthogonal mode)
+      m.m2bh1 = -m.m2bh1;
+      m.m2bh2 = -m.m2bh2;
+      m.m2bx1 = -m.m2bx1;
+      m.m2bx2 = -m.m2bx2;
+    }
     ensure(pb, pair_budget(pb));
     const MeshInfo mi{pb.n1, pb.n2, pb.n3, nb, P, nb};
     const MeshInfo miT{pb.n1, pb.n2, pb.n3, nb, P, nbt};   // target passes
@@ -2052,6 +2072,13 @@ struct EngineT : Engine {
     R* H5A[2] = {h5a0.p, h5a1.p};
     const double* W[2] = {sh.w.p, sh.w.p + P};
     const size_t cofs = size_t(2) * P * npm;   // doubles per channel in coefficient arrays
+    // biorthogonal mode: the bras of each channel are its left orbitals chi (TC mode: psi)
+    const bool bitc = pb.bitc;
+    cx<R>* CHI[2] = {chi.p, chi1.p};
+    const cx<R>* XS[2] = {bitc ? chi.p : psi.p, bitc ? chi1.p : psi1.p};
+    cx<R>* H5C[2] = {h5c.p, h5c_1.p};     // complex h5, parallel- and antiparallel-channel parts
+    cx<R>* H5CA[2] = {h5ca0.p, h5ca1.p};
+    cx<R>* HBC[2] = {H3bc.p, H3bc_1.p};   // conj(H3b), then its lattice components
     Events ev(6);
     double msA = 0, msB = 0;
     ev.rec(0, s);
@@ -2071,6 +2098,14 @@ struct EngineT : Engine {
       });
       fft3d_t<R, N>(PSI[sp], P, +1, s, pf);
       fft3d_t<R, N>(DD[sp], 3L * P, +1, s, pf);
+      if (bitc) {
+        TC_HIP(hipMemsetAsync(CHI[sp], 0, size_t(P) * NR * sizeof(cx<R>), s));
+        K(TC_K_SCATTER, 0.0, [&] {
+          hipLaunchKernelGGL((k_scatter<R>), dim3(gsc), dim3(256), 0, s, sh.coefL.p + sp * cofs, sh.boxidx.p,
+                             sh.npw.p, sh.kg.p, nb, npm, P, -1, CHI[sp], NR);
+        });
+        fft3d_t<R, N>(CHI[sp], P, +1, s, pf);
+      }
       K(TC_K_OTHER, 6.0 * fb * P, [&] {
         hipLaunchKernelGGL((k_lattice3<R, N>), dim3(nblk(long(P) * NR)), dim3(256), 0, s, DD[sp], DL[sp], bm, long(P),
                            NR, long(P) * NR);
@@ -2083,7 +2118,7 @@ struct EngineT : Engine {
     for (int sp = 0; sp < 2; ++sp) {
       TC_HIP(hipMemsetAsync(LOC[sp], 0, 8 * NR * sizeof(cx<R>), s));
       K(TC_K_OTHER, fb * (4.0 * P + 4.0), [&] {
-        hipLaunchKernelGGL((k_density<R, N>), dim3(nblk(NR)), dim3(256), 0, s, PSI[sp], PSI[sp], DD[sp], W[sp], P,
+        hipLaunchKernelGGL((k_density<R, N>), dim3(nblk(NR)), dim3(256), 0, s, XS[sp], PSI[sp], DD[sp], W[sp], P,
                            NJ[sp], NJ[sp] + NR);
       });
       TC_HIP(hipMemcpyAsync(wk2.p + 4 * sp * NR, NJ[sp], 4 * NR * sizeof(cx<R>), hipMemcpyDeviceToDevice, s));
@@ -2124,6 +2159,11 @@ struct EngineT : Engine {
       TC_HIP(hipMemsetAsync(H3[sp], 0, size_t(3) * P * NR * sizeof(cx<R>), s));
       TC_HIP(hipMemsetAsync(H5P[sp], 0, size_t(P) * NR * sizeof(R), s));
       TC_HIP(hipMemsetAsync(H5A[sp], 0, size_t(P) * NR * sizeof(R), s));
+      if (bitc) {
+        TC_HIP(hipMemsetAsync(HBC[sp], 0, size_t(3) * P * NR * sizeof(cx<R>), s));
+        TC_HIP(hipMemsetAsync(H5C[sp], 0, size_t(P) * NR * sizeof(cx<R>), s));
+        TC_HIP(hipMemsetAsync(H5CA[sp], 0, size_t(P) * NR * sizeof(cx<R>), s));
+      }
     }
     if (need_occ) {
       for (int s2 = 0; s2 < 2; ++s2)
@@ -2131,6 +2171,34 @@ struct EngineT : Engine {
           const int nt = std::min(T, P - a0);
           const long npair = long(nt) * P;
           const FusedArgs fa{P, nt, a0, S, chunk};
+          if (bitc) {
+            // rho21 = conj(chi_a) psi_b and rho12 = conj(chi_b) psi_a of channel s2 (as in the unpolarised
+            // biorthogonal pass), h5 split by kernel channel
+            cx<R>* in12 = bufA.p + npair * NR;
+            cx<R>* out12 = bufB.p + 4 * npair * NR;
+            K(TC_K_XY_PAIR_OCC, fb * 2.0 * (npair + nt + P), [&] {
+              hipLaunchKernelGGL((k_pair_xy<R, N, true>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, XS[s2],
+                                 PSI[s2], fa, bufA.p);
+              hipLaunchKernelGGL((k_pair_xy<R, N, false>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, XS[s2],
+                                 PSI[s2], fa, in12);
+            });
+            K(TC_K_ZCONV_OCC, 2.0 * (fb * 5.0 * npair + tabB), [&] {
+              zconv<OP_O>(s, bufA.p, bufB.p, npair, a0, mi, tb, 0);
+              zconv<OP_O>(s, in12, out12, npair, a0, mi, tb, 1);
+            });
+            K(TC_K_FUSED_OB, fb * (8.0 * npair + 2.0 * P) + 8.0 * fb * nt * S, [&] {
+              hipLaunchKernelGGL((k_fused_OB<R, N, true>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, bufB.p, out12,
+                                 PSI[s2], XS[s2], W[s2], fa, mi, rc, dfr.p, h5cpart.p, H3part.p, Hbpart.p, -1L, 4L,
+                                 -1L, 4L);
+            });
+            K(TC_K_SUM_PARTS, 8.0 * fb * nt * (S + 1), [&] {
+              hipLaunchKernelGGL((k_sum_parts_ob<R, N>), dim3(nblk(long(nt) * NR)), dim3(256), 0, s, S, nt, a0,
+                                 h5cpart.p, H3part.p, Hbpart.p, H5C[s2], H3[s2], HBC[s2]);
+              hipLaunchKernelGGL((k_sum_cx_parts<R, N>), dim3(nblk(long(nt) * NR)), dim3(256), 0, s, S, nt, a0,
+                                 h5cpart.p + size_t(S) * nt * NR, H5CA[s2]);
+            });
+            continue;
+          }
           K(TC_K_XY_PAIR_OCC, fb * (npair + nt + P), [&] {
             hipLaunchKernelGGL((k_pair_xy<R, N, true>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, PSI[s2], PSI[s2],
                                fa, bufA.p);
@@ -2152,15 +2220,23 @@ struct EngineT : Engine {
       // M_s2 = sum w conj(H3a4) psi per channel (3b2 sources), then h6 and the 3b2 field per target spin
       for (int s2 = 0; s2 < 2; ++s2)
         K(TC_K_OTHER, fb * (5.0 * P + 4.0), [&] {
-          hipLaunchKernelGGL((k_reduce_occ<R, N, R>), dim3(nblk(NR)), dim3(256), 0, s, H5P[s2], H3[s2], PSI[s2], W[s2],
-                             P, LOC[s2] + 6 * NR, wk2.p + (8 + 3 * s2) * NR);
+          if (bitc)
+            hipLaunchKernelGGL((k_reduce_occ<R, N, cx<R>>), dim3(nblk(NR)), dim3(256), 0, s, H5C[s2], HBC[s2],
+                               PSI[s2], W[s2], P, LOC[s2] + 6 * NR, wk2.p + (8 + 3 * s2) * NR);
+          else
+            hipLaunchKernelGGL((k_reduce_occ<R, N, R>), dim3(nblk(NR)), dim3(256), 0, s, H5P[s2], H3[s2], PSI[s2],
+                               W[s2], P, LOC[s2] + 6 * NR, wk2.p + (8 + 3 * s2) * NR);
         });
       fft3d_t<R, N>(wk2.p + 8 * NR, 6, -1, s, pf);
       for (int sp = 0; sp < 2; ++sp) {
         const int o = 1 - sp;
         K(TC_K_OTHER, fb * (2.0 * P + 1.0), [&] {
-          hipLaunchKernelGGL((k_h6_pol<R, N>), dim3(nblk(NR)), dim3(256), 0, s, H5P[sp], W[sp], H5A[o], W[o], P,
-                             LOC[sp] + 6 * NR);
+          if (bitc)
+            hipLaunchKernelGGL((k_h6_pol_c<R, N>), dim3(nblk(NR)), dim3(256), 0, s, H5C[sp], W[sp], H5CA[o], W[o], P,
+                               LOC[sp] + 6 * NR);
+          else
+            hipLaunchKernelGGL((k_h6_pol<R, N>), dim3(nblk(NR)), dim3(256), 0, s, H5P[sp], W[sp], H5A[o], W[o], P,
+                               LOC[sp] + 6 * NR);
           hipLaunchKernelGGL((k_gdiv2<R, N>), dim3(nblk(NR)), dim3(256), 0, s, rc, tHUp.p, tHUa.p,
                              wk2.p + (8 + 3 * sp) * NR, wk2.p + (8 + 3 * o) * NR, wk.p);
         });
@@ -2172,6 +2248,9 @@ struct EngineT : Engine {
       K(TC_K_OTHER, 6.0 * fb * P, [&] {
         hipLaunchKernelGGL((k_lattice3<R, N>), dim3(nblk(long(P) * NR)), dim3(256), 0, s, H3[sp], HL[sp], bm, long(P),
                            3 * NR, NR);
+        if (bitc)   // in place: B conj(H3b), the pass-B partner field
+          hipLaunchKernelGGL((k_lattice3<R, N>), dim3(nblk(long(P) * NR)), dim3(256), 0, s, HBC[sp], HBC[sp], bm,
+                             long(P), 3 * NR, NR);
       });
     ev.rec(3, s);
 
@@ -2210,16 +2289,21 @@ struct EngineT : Engine {
         if (need_A) {
           const FusedArgs fa{P, nt, t0, S, chunk};
           K(TC_K_XY_PAIR_TGT, fb * (npair + nt + P), [&] {
-            hipLaunchKernelGGL((k_pair_xy<R, N, false>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, PSI[sp],
+            hipLaunchKernelGGL((k_pair_xy<R, N, false>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, XS[sp],
                                tP, fa, bufA.p);
           });
           K(TC_K_ZCONV_A1, fb * 6.0 * npair + tabB, [&] {
             zconv<OP_A1>(s, npair, t0, miT, tb, 1);
           });
           K(TC_K_FUSED_A, fb * ((m.m3b6 ? 9.0 : 5.0) * npair + 8.0 * P + nt) + 6.0 * part, [&] {
-            hipLaunchKernelGGL((k_fused_A<R, N, true, false>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, bufB.p, PSI[sp],
-                               DL[sp], HL[sp], NJ[sp], W[sp], fa, m, int(m.m3b6 != 0), miT, bm, mm, dfr.p, bufA.p,
-                               gpart.p, h4part.p, NJ[o]);
+            if (bitc)   // complex densities
+              hipLaunchKernelGGL((k_fused_A<R, N, true, true>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, bufB.p,
+                                 PSI[sp], DL[sp], HL[sp], NJ[sp], W[sp], fa, m, int(m.m3b6 != 0), miT, bm, mm, dfr.p,
+                                 bufA.p, gpart.p, h4part.p, NJ[o]);
+            else
+              hipLaunchKernelGGL((k_fused_A<R, N, true, false>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, bufB.p,
+                                 PSI[sp], DL[sp], HL[sp], NJ[sp], W[sp], fa, m, int(m.m3b6 != 0), miT, bm, mm, dfr.p,
+                                 bufA.p, gpart.p, h4part.p, NJ[o]);
           });
           K(TC_K_SUM_PARTS, 6.0 * part + 6.0 * fd * nt + 3.0 * fb * nt, [&] {
             hipLaunchKernelGGL((k_sum_parts<R, N>), dim3(nblk(long(nt) * NR)), dim3(256), 0, s, 1, S, nt, t0, 0,
@@ -2251,8 +2335,8 @@ struct EngineT : Engine {
                                LOC[sp] + NR, h4.p, t0, nt, NTG, m, bm, Z.p);
           });
           K(TC_K_XY_PASSB, fb * (2.0 * npair + 4.0 * P + 4.0 * nt), [&] {
-            hipLaunchKernelGGL((k_passB_xy<R, N>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, tP, PSI[sp], Z.p,
-                               HL[sp], fy, miT, dfr.p, R(m.m3b5), srcB);
+            hipLaunchKernelGGL((k_passB_xy<R, N>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, tP, XS[sp], Z.p,
+                               bitc ? HBC[sp] : HL[sp], fy, miT, dfr.p, R(m.m3b5), srcB);
           });
           if (merged) {
             K(TC_K_ZCONV_A2, fb * 7.0 * npair + tabB, [&] {
@@ -2277,7 +2361,7 @@ struct EngineT : Engine {
           hipLaunchKernelGGL((k_local<R, N>), dim3(nblk(long(nt) * NR)), dim3(256), 0, s, tP, tD, LOC[sp],
                              h4.p, t0, nt, NTG, m, acc.p, g.p);
           if (!ts)
-            hipLaunchKernelGGL((k_epart<R, N>), dim3(kAccSlots * nt), dim3(256), 0, s, PSI[sp], acc.p, t0, nt,
+            hipLaunchKernelGGL((k_epart<R, N>), dim3(kAccSlots * nt), dim3(256), 0, s, XS[sp], acc.p, t0, nt,
                                sh.epart.p + size_t(kAccSlots) * sp * P);
         });
         fft3d_t<R, N>(g.p, nt, -1, s, pf);
@@ -2296,8 +2380,8 @@ struct EngineT : Engine {
     K(TC_K_CORR, 0.0, [&] {
       if (!ts) {
         for (int sp = 0; sp < 2; ++sp)
-          hipLaunchKernelGGL(k_kinetic, dim3(P), dim3(256), 0, s, sh.coef.p + sp * cofs, sh.coef.p + sp * cofs,
-                             sh.kg.p, sh.npw.p, nb, npm, sh.tkin.p + size_t(sp) * P);
+          hipLaunchKernelGGL(k_kinetic, dim3(P), dim3(256), 0, s, (bitc ? sh.coefL.p : sh.coef.p) + sp * cofs,
+                             sh.coef.p + sp * cofs, sh.kg.p, sh.npw.p, nb, npm, sh.tkin.p + size_t(sp) * P);
         TC_HIP(hipMemsetAsync(sh.ecorr.p, 0, size_t(4) * P * sizeof(double), s));
       }
       if (need_corr(pb, m)) corrections_pol(s, sh, pb, m, ts);
@@ -2323,6 +2407,12 @@ struct EngineT : Engine {
     const int P = pb.P(), nb = pb.nb, nk = pb.nk, npm = pb.npw_max;
     const size_t cofs = size_t(2) * P * npm;
     cx<double>* PS64[2] = {psi64.p, psi64_1.p};
+    // biorthogonal mode: overlaps S(a,b) = <chi_a|psi_b>, densities and 3a2 sources with conj(chi), energies
+    // with <chi| (each channel with its own left set)
+    const bool bitc = pb.bitc;
+    cx<double>* CH64[2] = {chi64.p, chi64_1.p};
+    const cx<double>* X64[2] = {bitc ? chi64.p : psi64.p, bitc ? chi64_1.p : psi64_1.p};
+    const double* CL[2] = {(bitc ? sh.coefL.p : sh.coef.p), (bitc ? sh.coefL.p : sh.coef.p) + cofs};
     // per channel: overlaps, FP64 fields, n~ and Y~ (v64p: [0,1] n~, [2,3] Y~, [4] F1, [5] F2)
     sh.S.alloc(size_t(4) * nk * nb * nb);
     std::vector<double> Sh(size_t(4) * nk * nb * nb);
@@ -2336,31 +2426,41 @@ struct EngineT : Engine {
     for (int sp = 0; sp < 2; ++sp) {
       const double* cf = sh.coef.p + sp * cofs;
       double* Ssp = sh.S.p + size_t(2) * sp * nk * nb * nb;
-      hipLaunchKernelGGL(k_overlap, dim3(nk * nb * nb), dim3(256), 0, s, cf, nb, cf, nb, sh.npw.p, npm, nk, Ssp);
+      hipLaunchKernelGGL(k_overlap, dim3(nk * nb * nb), dim3(256), 0, s, CL[sp], nb, cf, nb, sh.npw.p, npm, nk, Ssp);
       TC_HIP(hipMemsetAsync(PS64[sp], 0, size_t(P) * NR * sizeof(cx<double>), s));
       hipLaunchKernelGGL((k_scatter<double>), dim3(nblk(long(P) * npm)), dim3(256), 0, s, cf, sh.boxidx.p, sh.npw.p,
                          sh.kg.p, nb, npm, P, -1, PS64[sp], NR);
       fft3d_t<double, N>(PS64[sp], P, +1, s);
-      hipLaunchKernelGGL((k_density64<N>), dim3(nblk(NR)), dim3(256), 0, s, PS64[sp], PS64[sp], sh.w.p + sp * P, P,
+      if (bitc) {
+        TC_HIP(hipMemsetAsync(CH64[sp], 0, size_t(P) * NR * sizeof(cx<double>), s));
+        hipLaunchKernelGGL((k_scatter<double>), dim3(nblk(long(P) * npm)), dim3(256), 0, s, CL[sp], sh.boxidx.p,
+                           sh.npw.p, sh.kg.p, nb, npm, P, -1, CH64[sp], NR);
+        fft3d_t<double, N>(CH64[sp], P, +1, s);
+      }
+      hipLaunchKernelGGL((k_density64<N>), dim3(nblk(NR)), dim3(256), 0, s, X64[sp], PS64[sp], sh.w.p + sp * P, P,
                          v64p.p + sp * NR);
-      hipLaunchKernelGGL((k_corr_Ysrc<N>), dim3(nblk(NR)), dim3(256), 0, s, PS64[sp], PS64[sp], Ssp, focc.p + sp * P,
+      hipLaunchKernelGGL((k_corr_Ysrc<N>), dim3(nblk(NR)), dim3(256), 0, s, X64[sp], PS64[sp], Ssp, focc.p + sp * P,
                          nk, nb, 1.0 / (nk * pb.omega), v64p.p + (2 + sp) * NR);
     }
     fft3d_t<double, N>(v64p.p, 4, -1, s);
     TC_HIP(hipMemcpyAsync(Sh.data(), sh.S.p, Sh.size() * sizeof(double), hipMemcpyDeviceToHost, s));
     TC_HIP(hipStreamSynchronize(s));
-    // per channel: n~(0) and sum_ab f_a f_b S(a,b) S(b,a) / Omega^2 (real in TC mode)
-    double n0[2] = {0, 0}, cs[2] = {0, 0};
+    // per channel: n~(0) and sum_ab f_a f_b S(a,b) S(b,a) / Omega^2 (real in TC mode, complex in the
+    // biorthogonal mode: imaginary parts n0i, csi)
+    double n0[2] = {0, 0}, cs[2] = {0, 0}, n0i[2] = {0, 0}, csi[2] = {0, 0};
     for (int sp = 0; sp < 2; ++sp) {
       const double* S = &Sh[size_t(2) * sp * nk * nb * nb];
       const double* f = sp == 0 ? pb.occ.data() : pb.occ_dn.data();
       for (int k = 0; k < nk; ++k)
         for (int a = 0; a < nb; ++a) {
           n0[sp] += f[k * nb + a] / nk * S[2 * ((k * nb + a) * nb + a)] / pb.omega;
+          n0i[sp] += f[k * nb + a] / nk * S[2 * ((k * nb + a) * nb + a) + 1] / pb.omega;
           for (int b = 0; b < nb; ++b) {
             const double* sab = &S[2 * ((k * nb + a) * nb + b)];
             const double* sba = &S[2 * ((k * nb + b) * nb + a)];
-            cs[sp] += f[k * nb + a] / nk * f[k * nb + b] * (sab[0] * sba[0] - sab[1] * sba[1]) / (pb.omega * pb.omega);
+            const double fab = f[k * nb + a] / nk * f[k * nb + b] / (pb.omega * pb.omega);
+            cs[sp] += fab * (sab[0] * sba[0] - sab[1] * sba[1]);
+            csi[sp] += fab * (sab[0] * sba[1] + sab[1] * sba[0]);
           }
         }
     }
@@ -2384,17 +2484,17 @@ struct EngineT : Engine {
                          sh.npw.p, nb, npm, 0, P, 1.0 / double(NR), Zg, NR);
       hipLaunchKernelGGL((k_gather<double>), dim3(nblk(long(P) * npm)), dim3(256), 0, s, prod64.p + size_t(P) * NR,
                          sh.boxidx.p, sh.npw.p, nb, npm, 0, P, 1.0 / double(NR), Wg, NR);
-      hipLaunchKernelGGL(k_overlap, dim3(nk * nb * nb), dim3(256), 0, s, cf, nb, Zg, nb, sh.npw.p, npm, nk, sh.O.p);
+      hipLaunchKernelGGL(k_overlap, dim3(nk * nb * nb), dim3(256), 0, s, CL[sp], nb, Zg, nb, sh.npw.p, npm, nk, sh.O.p);
       // channel prefactors: pair(sp, sp) = parallel, pair(sp, o) = antiparallel
       const double c1a_p = kFourPi * corrB[0], c1a_a = kFourPi * corrB[1];
       const double c1s_p = 2 * kPi * corrB[0], c1s_a = 2 * kPi * corrB[1];
-      const double const1 = c1a_p * cs[sp] + c1a_a * cs[o];
-      const double c1sn0 = c1s_p * n0[sp] + c1s_a * n0[o];
+      const double const1 = c1a_p * cs[sp] + c1a_a * cs[o], const1i = c1a_p * csi[sp] + c1a_a * csi[o];
+      const double c1sn0 = c1s_p * n0[sp] + c1s_a * n0[o], c1sn0i = c1s_p * n0i[sp] + c1s_a * n0i[o];
       if (!ts) {
         hipLaunchKernelGGL(k_corr_apply, dim3(nblk(long(P) * npm)), dim3(256), 0, s, cf, cf, Ssp, sh.O.p, Zg, Wg,
                            focc.p + sp * P, sh.npw.p, nb, nb, npm, P, pb.omega, 1.0, dgb_eff(pb, m, corrA[0]), m.m3a2,
-                           const1, 0.0, m.m3b6, c1sn0, 0.0, sh.dhc2.p + sp * cofs, sh.dhc3.p + sp * cofs);
-        hipLaunchKernelGGL(k_corr_add, dim3(P), dim3(256), 0, s, cf, sh.dhc2.p + sp * cofs, sh.dhc3.p + sp * cofs,
+                           const1, const1i, m.m3b6, c1sn0, c1sn0i, sh.dhc2.p + sp * cofs, sh.dhc3.p + sp * cofs);
+        hipLaunchKernelGGL(k_corr_add, dim3(P), dim3(256), 0, s, CL[sp], sh.dhc2.p + sp * cofs, sh.dhc3.p + sp * cofs,
                            sh.npw.p, nb, npm, sh.out.p + sp * cofs, sh.ecorr.p + size_t(2) * sp * P);
         continue;
       }
@@ -2418,12 +2518,14 @@ struct EngineT : Engine {
                          sh.npw.p, nv, npm, 0, NT, 1.0 / double(NR), sh.ZgT.p, NR);
       hipLaunchKernelGGL((k_gather<double>), dim3(nblk(long(NT) * npm)), dim3(256), 0, s, prodT.p + size_t(NT) * NR,
                          sh.boxidx.p, sh.npw.p, nv, npm, 0, NT, 1.0 / double(NR), sh.WgT.p, NR);
-      hipLaunchKernelGGL(k_overlap, dim3(nk * nb * nv), dim3(256), 0, s, cf, nb, tcf, nv, sh.npw.p, npm, nk, sh.ST.p);
-      hipLaunchKernelGGL(k_overlap, dim3(nk * nb * nv), dim3(256), 0, s, cf, nb, sh.ZgT.p, nv, sh.npw.p, npm, nk,
+      hipLaunchKernelGGL(k_overlap, dim3(nk * nb * nv), dim3(256), 0, s, CL[sp], nb, tcf, nv, sh.npw.p, npm, nk,
+                         sh.ST.p);
+      hipLaunchKernelGGL(k_overlap, dim3(nk * nb * nv), dim3(256), 0, s, CL[sp], nb, sh.ZgT.p, nv, sh.npw.p, npm, nk,
                          sh.OT.p);
       hipLaunchKernelGGL(k_corr_apply, dim3(nblk(long(NT) * npm)), dim3(256), 0, s, tcf, cf, sh.ST.p, sh.OT.p, Zg,
                          sh.WgT.p, focc.p + sp * P, sh.npw.p, nb, nv, npm, NT, pb.omega, 1.0,
-                         dgb_eff(pb, m, corrA[0]), m.m3a2, const1, 0.0, m.m3b6, c1sn0, 0.0, sh.dhc2T.p, sh.dhc3T.p);
+                         dgb_eff(pb, m, corrA[0]), m.m3a2, const1, const1i, m.m3b6, c1sn0, c1sn0i, sh.dhc2T.p,
+                         sh.dhc3T.p);
       hipLaunchKernelGGL(k_corr_add, dim3(NT), dim3(256), 0, s, tcf, sh.dhc2T.p, sh.dhc3T.p, sh.npw.p, nv, npm,
                          ts->out + sp * nc, sh.ecorrT.p);
     }
@@ -3356,17 +3458,18 @@ int prepare(tc_ctx* c) {
       return fail(c, TC_ERR_STATE, "orbitals of k-point " + std::to_string(k) + " not loaded");
     nleft += pb.left[k];
   }
-  if (pb.nsym > 0 && (nleft != 0 || pb.nspin == 2))
-    return fail(c, TC_ERR_UNSUPPORTED, "symmetry is built for TC mode with one spin channel");
-  if (nleft != 0 && nleft != pb.nk)
-    return fail(c, TC_ERR_STATE, "left orbitals are loaded for some k-points only");
-  pb.bitc = nleft == pb.nk;
   if (pb.nspin == 2) {
-    for (int k = 0; k < pb.nk; ++k)
+    for (int k = 0; k < pb.nk; ++k) {
       if (!pb.loaded_dn[k])
         return fail(c, TC_ERR_STATE, "down-spin orbitals of k-point " + std::to_string(k) + " not loaded");
-    if (pb.bitc) return fail(c, TC_ERR_UNSUPPORTED, "spin-polarised runs are built for TC mode (no left orbitals)");
+      nleft += pb.left_dn[k];
+    }
   }
+  if (pb.nsym > 0 && (nleft != 0 || pb.nspin == 2))
+    return fail(c, TC_ERR_UNSUPPORTED, "symmetry is built for TC mode with one spin channel");
+  if (nleft != 0 && nleft != pb.nspin * pb.nk)
+    return fail(c, TC_ERR_STATE, "left orbitals are loaded for some k-points or spin channels only");
+  pb.bitc = nleft != 0;
   if (!c->eng || c->eng_prec != pb.prec || c->eng_N != pb.N) {
     if (pb.prec == TC_PREC_FP32_SPLITBF16 && pb.N % 8 != 0)
       return fail(c, TC_ERR_UNSUPPORTED, "split-BF16 DFT stages need a grid length divisible by 8");
@@ -3602,7 +3705,8 @@ int do_backward(tc_ctx* c, void* grad_dev, double* grad_host, double* dA, double
       c->tables_dirty = true;
       c->eng->upload_tables(pb, TableVariant{});
       run_apply(c, nullptr, nullptr);
-      finish(2.0, gl_dev, gl_host);
+      // 2 dE/dchi* per channel: one spin channel per orbital set when polarised, both otherwise
+      finish(pb.nspin == 2 ? 1.0 : 2.0, gl_dev, gl_host);
     }
     if (grad_dev || grad_host) {
       std::swap(sh.coef.p, sh.coefL.p);
@@ -3612,7 +3716,7 @@ int do_backward(tc_ctx* c, void* grad_dev, double* grad_host, double* dA, double
       c->tables_dirty = true;
       c->eng->upload_tables(pb, TableVariant{TableVariant::ADJOINT, 0, 0.0});
       run_apply(c, nullptr, nullptr);
-      finish(2.0, grad_dev, grad_host);
+      finish(pb.nspin == 2 ? 1.0 : 2.0, grad_dev, grad_host);
       std::swap(sh.coef.p, sh.coefL.p);
       std::swap(sh.coef.n, sh.coefL.n);
       keep.swapped = false;
@@ -3688,6 +3792,7 @@ int begin_load(tc_ctx* c, int ik, int nband, const double* occ, int spin = 0) {
     std::fill(pb.loaded.begin(), pb.loaded.end(), 0);
     std::fill(pb.left.begin(), pb.left.end(), 0);
     std::fill(pb.loaded_dn.begin(), pb.loaded_dn.end(), 0);
+    std::fill(pb.left_dn.begin(), pb.left_dn.end(), 0);
   }
   int mx = 0;
   for (int k = 0; k < pb.nk; ++k) mx = std::max(mx, pb.npw[k]);
@@ -3733,7 +3838,7 @@ int biorthogonalize_at(tc_ctx* c, int ik, int nb, double* right, double* lout) {
 int biorthogonalize(tc_ctx* c, int ik) {
   Problem& pb = c->pb;
   const size_t off = size_t(2) * ik * pb.nb * pb.npw_max;
-  c->sh.coefL.alloc(size_t(2) * pb.P() * pb.npw_max);
+  c->sh.coefL.alloc(size_t(2) * pb.nspin * pb.P() * pb.npw_max);   // spin-major, as the right coefficients
   return biorthogonalize_at(c, ik, pb.nb, c->sh.coef.p + off, c->sh.coefL.p + off);
 }
 
@@ -3749,6 +3854,7 @@ void load_set(tc_ctx* c, const double* r, const double* l, int nbx, const std::v
   if (pb.nspin == 2) {
     pb.occ_dn.assign(occ.begin() + per, occ.begin() + 2 * per);
     std::fill(pb.loaded_dn.begin(), pb.loaded_dn.end(), 1);
+    std::fill(pb.left_dn.begin(), pb.left_dn.end(), l ? 1 : 0);
   }
   std::fill(pb.loaded.begin(), pb.loaded.end(), 1);
   std::fill(pb.left.begin(), pb.left.end(), l ? 1 : 0);
@@ -3883,7 +3989,7 @@ int do_scf(tc_ctx* c, const tc_scf_params& prm, double* ehist, int* niter) {
       sh.bo_l.alloc(kb);
       for (int k = 0; k < nk; ++k) {
         TC_HIP(hipMemcpyAsync(sh.bo_l.p, new_l + k * kb, kb * sizeof(double), hipMemcpyDeviceToDevice, s));
-        st = biorthogonalize_at(c, k, nb, new_r + k * kb, new_l + k * kb);
+        st = biorthogonalize_at(c, k % pb.nk, nb, new_r + k * kb, new_l + k * kb);   // block k: channel k / nk
         if (st != TC_OK) return st;
       }
     }
@@ -3934,7 +4040,8 @@ int get_orbitals(tc_ctx* c, int spin, int ik, double* right, double* left) {
   if (ik < 0 || ik >= pb.nk) return fail(c, TC_ERR_ARG, "k-point index out of range");
   if (spin < 0 || spin >= pb.nspin) return fail(c, TC_ERR_ARG, "spin channel out of range");
   if (!(spin == 0 ? pb.loaded[ik] : pb.loaded_dn[ik])) return fail(c, TC_ERR_STATE, "orbitals of this k-point are not loaded");
-  if (left && (spin != 0 || !pb.left[ik])) return fail(c, TC_ERR_STATE, "no left orbitals on this k-point");
+  if (left && !(spin == 0 ? pb.left[ik] : pb.left_dn[ik]))
+    return fail(c, TC_ERR_STATE, "no left orbitals on this k-point");
   const int nb = pb.nb, npw = pb.npw[ik], npm = pb.npw_max;
   std::vector<double> buf(size_t(2) * nb * npm);
   for (int side = 0; side < 2; ++side) {
@@ -4030,6 +4137,7 @@ int tc_set_kmesh(tc_ctx* c, int n1, int n2, int n3) {
     pb.loaded.assign(pb.nk, 0);
     pb.left.assign(pb.nk, 0);
     pb.loaded_dn.assign(pb.nk, 0);
+    pb.left_dn.assign(pb.nk, 0);
     pb.nb = 0;
     pb.nsym = 0;
     pb.nkb = 0;   // band k-points are coded after the mesh ones
@@ -4146,6 +4254,7 @@ int tc_set_nspin(tc_ctx* c, int nspin) {
     std::fill(pb.loaded.begin(), pb.loaded.end(), 0);
     std::fill(pb.left.begin(), pb.left.end(), 0);
     pb.loaded_dn.assign(pb.nk, 0);
+    pb.left_dn.assign(pb.nk, 0);
     c->have_result = false;
     return TC_OK;
   });
@@ -4178,19 +4287,31 @@ int tc_load_orbitals_spin(tc_ctx* c, int spin, int ik, int nband, const double* 
     Problem& pb = c->pb;
     if (spin != 1) return fail(c, TC_ERR_ARG, "spin must be 0 or 1");
     if (pb.nspin != 2) return fail(c, TC_ERR_STATE, "tc_set_nspin(ctx, 2) first");
-    if (left) return fail(c, TC_ERR_UNSUPPORTED, "spin-polarised runs are built for TC mode (no left orbitals)");
     if (!right) return fail(c, TC_ERR_ARG, "null coefficients");
     int st = begin_load(c, ik, nband, occ, 1);
     if (st != TC_OK) return st;
     const int npw = pb.npw[ik];
     pb.loaded_dn[ik] = 0;
+    pb.left_dn[ik] = 0;
     c->have_result = false;
     std::vector<double> stage(size_t(2) * nband * pb.npw_max, 0.0);
-    for (int b = 0; b < nband; ++b)
-      std::memcpy(&stage[size_t(2) * b * pb.npw_max], right + size_t(2) * b * npw, size_t(2) * npw * sizeof(double));
-    TC_HIP(hipMemcpy(c->sh.coef.p + size_t(2) * (pb.P() + size_t(ik) * nband) * pb.npw_max, stage.data(),
-                     stage.size() * sizeof(double), hipMemcpyHostToDevice));
+    auto pack = [&](const double* src) {
+      for (int b = 0; b < nband; ++b)
+        std::memcpy(&stage[size_t(2) * b * pb.npw_max], src + size_t(2) * b * npw, size_t(2) * npw * sizeof(double));
+    };
+    pack(right);
+    const size_t off = size_t(2) * (pb.P() + size_t(ik) * nband) * pb.npw_max;   // channel 1, k-point ik
+    TC_HIP(hipMemcpy(c->sh.coef.p + off, stage.data(), stage.size() * sizeof(double), hipMemcpyHostToDevice));
     upload_basis_data(c);
+    if (left) {   // biorthogonalised within the channel, as for channel 0
+      pack(left);
+      c->sh.bo_l.alloc(stage.size());
+      TC_HIP(hipMemcpy(c->sh.bo_l.p, stage.data(), stage.size() * sizeof(double), hipMemcpyHostToDevice));
+      c->sh.coefL.alloc(size_t(2) * pb.nspin * pb.P() * pb.npw_max);
+      st = biorthogonalize_at(c, ik, nband, c->sh.coef.p + off, c->sh.coefL.p + off);
+      if (st != TC_OK) return st;
+      pb.left_dn[ik] = 1;
+    }
     pb.loaded_dn[ik] = 1;
     return TC_OK;
   });

@@ -297,6 +297,22 @@ __global__ void k_h6_pol(const R* h5p, const double* w, const R* h5ao, const dou
   h6[r] = mk<R>(R(s), R(0));
 }
 
+// the same with the complex h5 of the biorthogonal mode
+template <typename R, int N>
+__global__ void k_h6_pol_c(const cx<R>* h5p, const double* w, const cx<R>* h5ao, const double* wo, int P,
+                           cx<R>* h6) {
+  constexpr long NR = long(N) * N * N;
+  const long r = long(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (r >= NR) return;
+  double sr = 0, si = 0;
+  for (int a = 0; a < P; ++a) {
+    const cx<R> u = h5p[long(a) * NR + r], v = h5ao[long(a) * NR + r];
+    sr += w[a] * double(u.x) + wo[a] * double(v.x);
+    si += w[a] * double(u.y) + wo[a] * double(v.y);
+  }
+  h6[r] = mk<R>(R(sr), R(si));
+}
+
 // ---------------------------------------------------------------- pair passes
 // Lattice components of the vector kernel.  With kappa_d = m_d + delta_d (grid frequency plus the
 // pair's shift Delta, both in units of the reciprocal rows b_d), Q_c = sum_d kappa_d B_dc.  The
@@ -403,6 +419,11 @@ struct Fz {
   static constexpr bool fits(int planes) { return planes * PLANE * int(sizeof(cx<R>)) <= kLdsMax; }
   static constexpr int kFitPlanes = kLdsMax / (PLANE * int(sizeof(cx<R>)));
   static constexpr int GRP = kFitPlanes < RB ? kFitPlanes : RB;   // one-plane-per-partner rounds
+  // k_pair_xy and k_fused_Y (one plane per partner, few registers): in FP32 at 48 points 4 planes per round
+  // (75 KB of LDS) at up to 6 waves per SIMD, so that two work-groups share a CU and overlap their phases
+  static constexpr bool TWO_WG = sizeof(R) == 4 && N == 48;
+  static constexpr int GRP1 = TWO_WG ? 4 : GRP;
+  static constexpr int WAVES1 = TWO_WG ? 6 : 1;
   static constexpr bool COMB = N == 48;                    // comb transforms, outputs in sigma order
   // the next partner's planes are loaded into registers while this partner's are transformed; at 48
   // points the register budget allows it in FP32 only, and k_fused_A measured faster without it there
@@ -638,20 +659,21 @@ struct PlaneWG {
 // batch: TFIRST a = t0 + t, b = q; else a = q, b = t0 + t.  out[(t P + q)][N^3].  bra holds the left
 // orbitals chi (the right ones, psi, in TC mode), ket the right ones.
 template <typename R, int N, bool TFIRST>
-__global__ void __launch_bounds__((Fz<R, N>::NTH)) k_pair_xy(const cx<R>* bra, const cx<R>* ket, FusedArgs fa,
+__global__ void __launch_bounds__((Fz<R, N>::NTH)) __attribute__((amdgpu_waves_per_eu(Fz<R, N>::WAVES1)))
+k_pair_xy(const cx<R>* bra, const cx<R>* ket, FusedArgs fa,
                                                            cx<R>* out) {
   using F = Fz<R, N>;
   constexpr int KP = F::KP, RB = F::RB;
   constexpr long NR = long(N) * N * N;
-  __shared__ cx<R> sm[F::GRP * F::PLANE];
+  __shared__ cx<R> sm[F::GRP1 * F::PLANE];
   const PlaneWG<R, N> wg(fa);
   const cx<R>* tf = TFIRST ? bra : ket;   // field of the target index
   const cx<R>* pf = TFIRST ? ket : bra;   // field of the partner index
   cx<R> pt[KP];
 #pragma unroll
   for (int i = 0; i < KP; ++i) pt[i] = tf[long(fa.t0 + wg.t) * NR + wg.zo + RB * N * i];
-  for (int q0 = wg.qb; q0 < wg.qe; q0 += F::GRP) {
-    const int nq = min(F::GRP, wg.qe - q0);
+  for (int q0 = wg.qb; q0 < wg.qe; q0 += F::GRP1) {
+    const int nq = min(F::GRP1, wg.qe - q0);
     for (int cc = 0; cc < nq; ++cc) {
       const cx<R>* pq = pf + long(q0 + cc) * NR + wg.zo;
 #pragma unroll
@@ -659,7 +681,7 @@ __global__ void __launch_bounds__((Fz<R, N>::NTH)) k_pair_xy(const cx<R>* bra, c
         sm[cc * F::PLANE + wg.so0 + RB * F::LD * i] = TFIRST ? cmulc(pt[i], pq[RB * N * i]) : cmulc(pq[RB * N * i], pt[i]);
     }
     __syncthreads();
-    planes_fft<R, N, -1>(sm, nq, threadIdx.x);
+    planes_fft<R, N, -1, true>(sm, nq, threadIdx.x);
     for (int cc = 0; cc < nq; ++cc) {
       cx<R>* dst = out + (long(wg.t) * fa.P + q0 + cc) * NR + wg.zo;
 #pragma unroll
@@ -673,8 +695,8 @@ __global__ void __launch_bounds__((Fz<R, N>::NTH)) k_pair_xy(const cx<R>* bra, c
 // m3b5 conj(Hl_qd) psi_t, with Zl = B (m2bx2 D_j - m3b3 h1 psi_j + m3b4 h4_j) and Hl = B conj(H3b)
 // (TC mode: chi = psi and H3b = conj(H3a4), so Hl = B H3a4); forward xy transformed:
 // out[(pair 2 + 0)] = kappa_1 T~_1 + kappa_2 T~_2, out[(pair 2 + 1)] = T~_3, pair = t P + q, Delta = k_t - k_q.
-// FP32 at 24^3: no register prefetch of the partner fields, 4 waves per SIMD instead (no spills); at 48
-// points none either (768-thread work-groups); elsewhere the prefetch
+// FP32 at 24^3: no register prefetch of the partner fields, 4 waves per SIMD instead (no spills); FP64 at 48
+// points none either (register budget); elsewhere the prefetch
 template <typename R, int N>
 constexpr bool kPassBPrefetch = !(sizeof(R) == 4 && N == 24) && Fz<R, N>::PREFETCH;
 template <typename R, int N>
@@ -1423,25 +1445,26 @@ k_fused_A(const cx<R>* buf5, const cx<R>* psi, const cx<R>* Dl, const cx<R>* Hl,
 
 // One field per pair (xy in G space): partial of coef sum_q w_q Y psi_q, GRP partners per round.
 template <typename R, int N>
-__global__ void __launch_bounds__((Fz<R, N>::NTH)) k_fused_Y(const cx<R>* buf1, const cx<R>* psi, const double* w,
+__global__ void __launch_bounds__((Fz<R, N>::NTH)) __attribute__((amdgpu_waves_per_eu(Fz<R, N>::WAVES1)))
+k_fused_Y(const cx<R>* buf1, const cx<R>* psi, const double* w,
                                                            FusedArgs fa, double coef, cx<R>* gpart) {
   using F = Fz<R, N>;
   constexpr int KP = F::KP, RB = F::RB;
   constexpr long NR = long(N) * N * N;
-  __shared__ cx<R> sm[F::GRP * F::PLANE];
+  __shared__ cx<R> sm[F::GRP1 * F::PLANE];
   const PlaneWG<R, N> wg(fa);
   cx<R> ga[KP];
 #pragma unroll
   for (int i = 0; i < KP; ++i) ga[i] = mk<R>(R(0), R(0));
-  for (int q0 = wg.qb; q0 < wg.qe; q0 += F::GRP) {
-    const int nq = min(F::GRP, wg.qe - q0);
+  for (int q0 = wg.qb; q0 < wg.qe; q0 += F::GRP1) {
+    const int nq = min(F::GRP1, wg.qe - q0);
     for (int cc = 0; cc < nq; ++cc) {
       const cx<R>* src = buf1 + (long(wg.t) * fa.P + q0 + cc) * NR + wg.zo;
 #pragma unroll
       for (int i = 0; i < KP; ++i) sm[cc * F::PLANE + wg.so0 + RB * F::LD * i] = src[RB * N * i];
     }
     __syncthreads();
-    planes_fft<R, N, 1>(sm, nq, threadIdx.x);
+    planes_fft<R, N, 1, true>(sm, nq, threadIdx.x);
 #pragma unroll
     for (int i = 0; i < KP; ++i) {
       const long r = wg.zo + RB * N * i;
@@ -1608,7 +1631,9 @@ struct PassOB {
 // sT < 0: the pair-major layout of the pass's own z stages (sT = 4P, sQ = 4).  With the resident store of
 // pass-A z-stage outputs ([pair][5], fields 1..4 as here): V21 of (a, b) is stored pair (t = b, q = a) and
 // V12 is stored pair (t = a, q = b).
-template <typename R, int N>
+// SPLITH (spin-polarised runs): the parallel- and antiparallel-channel parts of h5 are kept apart, the
+// antiparallel one in the second half of h5part ([2][S][T][N^3]), as in k_fused_O.
+template <typename R, int N, bool SPLITH = false>
 __global__ void __launch_bounds__((Fz<R, N>::NTH)) __attribute__((amdgpu_waves_per_eu(PassOB<R, N>::WAVES)))
 k_fused_OB(const cx<R>* buf21, const cx<R>* buf12,
                                                             const cx<R>* psi, const cx<R>* chi, const double* w,
@@ -1626,10 +1651,11 @@ k_fused_OB(const cx<R>* buf21, const cx<R>* buf12,
   const PlaneWG<R, N> wg(fa);
   const Basis<R> B = basis<R>(rc);
   const int ja = fa.t0 + wg.t;
-  cx<R> h5[KP], H[KP][3], Hb[KP][3], X21[KP][3];
+  cx<R> h5[KP], h5b[SPLITH ? KP : 1], H[KP][3], Hb[KP][3], X21[KP][3];
 #pragma unroll
   for (int i = 0; i < KP; ++i) {
     h5[i] = mk<R>(R(0), R(0));
+    if constexpr (SPLITH) h5b[i] = mk<R>(R(0), R(0));
 #pragma unroll
     for (int c = 0; c < 3; ++c) H[i][c] = Hb[i][c] = mk<R>(R(0), R(0));
   }
@@ -1703,8 +1729,13 @@ k_fused_OB(const cx<R>* buf21, const cx<R>* buf12,
 #pragma unroll
             for (int d = 0; d < 3; ++d) Y[d] = sm[(base + d) * PL + so];
             to_cart(B, Y, X12);
+            cx<R> hv = X21[i][0] * X12[0];
 #pragma unroll
-            for (int c = 0; c < 3; ++c) h5[i] = h5[i] + wq * (X21[i][c] * X12[c]);
+            for (int c = 1; c < 3; ++c) hv = hv + X21[i][c] * X12[c];
+            if (SPLITH && ch == 1)
+              h5b[i] = h5b[i] + wq * hv;
+            else
+              h5[i] = h5[i] + wq * hv;
             if (ch == 0) {
 #pragma unroll
               for (int c = 0; c < 3; ++c) {
@@ -1723,6 +1754,7 @@ k_fused_OB(const cx<R>* buf21, const cx<R>* buf12,
     const long r = wg.zo + RB * N * i;
     const long o = long(wg.c) * fa.T + wg.t;
     h5part[o * NR + r] = h5[i];
+    if constexpr (SPLITH) h5part[(long(fa.S + wg.c) * fa.T + wg.t) * NR + r] = h5b[i];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       H3part[(o * 3 + c) * NR + r] = H[i][c];
@@ -1742,6 +1774,23 @@ __global__ void k_sum_real_parts(int S, int T, int t0, const R* parts, R* out) {
   double s = 0;
   for (int c = 0; c < S; ++c) s += double(parts[(long(c) * T + t) * NR + r]);
   out[long(t0 + t) * NR + r] = R(s);
+}
+
+// Fixed-order FP64 sum of complex partner-chunk partials: out[t0 + t] = sum_c parts[c][t]
+template <typename R, int N>
+__global__ void k_sum_cx_parts(int S, int T, int t0, const cx<R>* parts, cx<R>* out) {
+  constexpr long NR = long(N) * N * N;
+  const long id = long(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (id >= long(T) * NR) return;
+  const int t = int(id / NR);
+  const long r = id - long(t) * NR;
+  double sr = 0, si = 0;
+  for (int c = 0; c < S; ++c) {
+    const cx<R> v = parts[(long(c) * T + t) * NR + r];
+    sr += double(v.x);
+    si += double(v.y);
+  }
+  out[long(t0 + t) * NR + r] = mk<R>(R(sr), R(si));
 }
 
 // Fixed-order FP64 sums of the partials of k_fused_OB: h5[t0+t], H3a4[t0+t], H3bc[t0+t].

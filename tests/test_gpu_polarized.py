@@ -3,9 +3,11 @@
 Against the FP64 oracle on the same inputs: every term of both spin channels, the totals, the energy
 and its parts, the orbital energies of both channels (FP64 and FP32), the gradient of each channel's
 coefficients and of A, C (autograd), each channel's operator on trial vectors, and the fixed point of
-the two-channel SCF loop (per-channel plane-wave matrices).  Independent of the oracle: two identical
-channels reproduce the unpolarised run and its SCF iterates, and exchanging the channels exchanges
-the outputs and keeps the energy.  Left orbitals in a polarised channel fail with TC_ERR_UNSUPPORTED.
+the two-channel SCF loop (per-channel plane-wave matrices); in the biorthogonal mode (a left set per
+channel) every term, the energy, the orbital energies, the right and left gradients and the trial
+vectors.  Independent of the oracle: two identical channels reproduce the unpolarised run and its SCF
+iterates (TC and biorthogonal), and exchanging the channels exchanges the outputs and keeps the energy.
+Left orbitals in one channel only fail with TC_ERR_STATE.
 """
 import numpy as np
 import pytest
@@ -38,6 +40,15 @@ CASES = {
                                                        occ_dn=[1.0, 0.0, 0.0]),
     "fcc_k121_g16_pol": lambda: T.polarized(T.tiny_fcc(kmesh=(1, 2, 1), grid=16, ecut=3.0, nb=2, a=7.0,
                                                        seed_offset=9), 34, mix=0.5),
+    # biorthogonal mode: a left set per channel
+    "fcc_k211_g8_bitc_pol": lambda: T.polarized(T.tiny_fcc(kmesh=(2, 1, 1), grid=8, ecut=2.0, nb=2, a=6.0,
+                                                           occ=[1.0, 0.7], left_mix=0.15, seed_offset=7), 35,
+                                                occ_dn=[0.9, 0.2]),
+    "fcc_k221_g12_bitc_pol_empty_band": lambda: T.polarized(T.tiny_fcc(kmesh=(2, 2, 1), grid=12, ecut=2.0, nb=3,
+                                                                       a=6.0, occ=[1.0, 0.8, 0.3], left_mix=0.1,
+                                                                       seed_offset=5), 37, occ_dn=[1.0, 0.0, 0.0]),
+    "fcc_k121_g16_bitc_pol": lambda: T.polarized(T.tiny_fcc(kmesh=(1, 2, 1), grid=16, ecut=3.0, nb=2, a=7.0,
+                                                            left_mix=0.2, seed_offset=9), 36, mix=0.5),
 }
 
 
@@ -130,12 +141,13 @@ def test_exchanging_channels_exchanges_outputs():
         assert relerr(outs[1][1 - s], outs[0][s]) < 1e-12
 
 
-def test_unsupported_calls_with_two_channels():
+def test_left_orbitals_in_one_channel_only_are_rejected():
     w = T.polarized(T.tiny_fcc(kmesh=(2, 1, 1), grid=8, ecut=2.0, nb=2, a=6.0, occ=[1.0, 0.7]), 9)
-    _say("[gpu] polarised unsupported calls")
+    _say("[gpu] polarised: left orbitals in the down channel only")
     op = tc.from_workload(w, precision=tc.TC_PREC_FP64)
-    with pytest.raises(tc.TCError, match="status"):   # left orbitals in a polarised channel
-        op.load_orbitals(0, w.right_dn[0], w.occ_dn[0], left=w.right_dn[0], spin=1)
+    op.load_orbitals(0, w.right_dn[0], w.occ_dn[0], left=w.right_dn[0], spin=1)
+    with pytest.raises(tc.TCError, match="status"):
+        op.apply()
     op.close()
     # a missing down channel is reported before any work
     op = tc.TCOperator()
@@ -266,3 +278,105 @@ def test_polarized_scf_fixed_point_vs_oracle():
     assert abs(E - Eo) < 1e-10 * abs(Eo)
     assert worst_r < 1e-6
     assert worst_e < 1e-6
+
+
+def _bitc_pol():
+    return CASES["fcc_k211_g8_bitc_pol"]()
+
+
+def test_bitc_identical_channels_reproduce_unpolarized_bitc():
+    """Two biorthogonal channels with the same pair and fillings: the unpolarised biorthogonal run."""
+    w = T.tiny_fcc(kmesh=(2, 2, 1), grid=12, ecut=2.0, nb=3, a=6.0, occ=[1.0, 0.9, 0.0], left_mix=0.1,
+                   seed_offset=5)
+    _say("[gpu] polarised biorthogonal, identical channels fcc_k221_g12")
+    op = tc.from_workload(w, precision=tc.TC_PREC_FP64)
+    ref = op.apply()
+    E0, _ = op.energy()
+    e0 = op.orbital_energies()
+    op.close()
+    wp = w.replace(right_dn=list(w.right), left_dn=list(w.left), occ_dn=list(w.occ))
+    op = tc.from_workload(wp, precision=tc.TC_PREC_FP64)
+    got = op.apply()
+    E1, _ = op.energy()
+    e1 = op.orbital_energies()
+    op.close()
+    for s in (0, 1):
+        assert relerr(got[s], ref) < 1e-12
+        assert np.abs(e1[s] - e0).max() < 1e-12 * np.abs(e0).max()
+    assert abs(E1 - E0) < 1e-12 * abs(E0)
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp32", 2e-6)])
+def test_bitc_polarized_gradients_vs_oracle(prec, tol):
+    """The right and left gradients of each channel (its own pair) and dA, dC against the oracle's
+    autograd at the biorthonormalised pairs."""
+    from oracle import grad as OG
+
+    w = _bitc_pol()
+    pairs = OG.bitc_pair_polarized(w)
+    E, gru, glu, grd, gld, gA, gC = OG.energy_and_grad_bitc_polarized(w, *pairs)
+    _say(f"[gpu] polarised biorthogonal backward {prec} vs oracle autograd")
+    op = tc.from_workload(w, precision=tc.TC_PREC_FP64 if prec == "fp64" else tc.TC_PREC_FP32)
+    Eg, _ = op.energy()
+    gr, gl, dA, dC = op.backward_lr()
+    op.close()
+    assert abs(Eg - E) < tol * abs(E)
+    for got, ref in ((gr[0], gru), (gr[1], grd), (gl[0], glu), (gl[1], gld)):
+        err = relerr(got, ref)
+        _say(f"    gradient error {err:.3e}")
+        assert err < tol
+    scale = max(np.abs(gA).max(), np.abs(gC).max())
+    assert np.abs(dA - gA).max() < tol * scale and np.abs(dC - gC).max() < tol * scale
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp32", 2e-6)])
+def test_bitc_polarized_trial_vectors_vs_oracle(prec, tol):
+    """tc_apply in the biorthogonal mode with two channels: the oracle takes each channel's
+    biorthonormalised pair and adds the vectors to that channel as bands of zero filling (right and left)."""
+    from oracle import grad as OG
+
+    w = _bitc_pol()
+    ru, lu, rd, ld = OG.bitc_pair_polarized(w)
+    rng = np.random.default_rng(7)
+    nv = 2
+    B = 2 * np.pi * np.linalg.inv(np.asarray(w.lattice)).T
+    env = [np.exp(-0.15 * np.sum(((w.kfrac[k][None, :] + m) @ B) ** 2, 1)) for k, m in enumerate(w.miller)]
+    vecs = [[(rng.standard_normal((nv, m.shape[0])) + 1j * rng.standard_normal((nv, m.shape[0]))) * e
+             for m, e in zip(w.miller, env)] for _ in range(2)]
+    cat = lambda a, v: [np.concatenate([x, y]) for x, y in zip(a, v)]
+    wx = w.replace(right=cat(ru, vecs[0]), left=cat(lu, vecs[0]), right_dn=cat(rd, vecs[1]),
+                   left_dn=cat(ld, vecs[1]), occ=[np.concatenate([o, np.zeros(nv)]) for o in w.occ],
+                   occ_dn=[np.concatenate([o, np.zeros(nv)]) for o in w.occ_dn])
+    pr = Problem(wx, biorthogonalize=False)
+    nb = w.right[0].shape[0]
+    ref = []
+    for s in (0, 1):
+        g = sum(MULT.get(t, 1) * pr.term(t, s) for t in ALL_TERMS)
+        ref.append([c.numpy()[nb:] for c in pr.to_coeff(g, s)])
+    _say(f"[gpu] polarised biorthogonal trial vectors {prec} vs oracle")
+    op = tc.from_workload(w, precision=tc.TC_PREC_FP64 if prec == "fp64" else tc.TC_PREC_FP32)
+    op.energy()
+    got = op.apply_vectors(vecs)
+    op.close()
+    scale = max(np.abs(x).max() for r in ref for x in r)
+    err = max(np.abs(a - b).max() for s in (0, 1) for a, b in zip(got[s], ref[s])) / scale
+    _say(f"    max element error / max |h v| = {err:.3e}")
+    assert err < tol
+
+
+def test_bitc_polarized_scf_with_equal_channels_follows_the_unpolarized_loop():
+    """Two identical biorthogonal channels: the two-channel BITC-SCF loop takes the unpolarised loop's
+    steps and energies."""
+    w = T.tiny_fcc(kmesh=(2, 1, 1), grid=8, ecut=2.0, nb=2, a=6.0, occ=[1.0, 0.7], left_mix=0.15, seed_offset=7)
+    wp = w.replace(right_dn=[c.copy() for c in w.right], left_dn=[c.copy() for c in w.left],
+                   occ_dn=[o.copy() for o in w.occ])
+    _say("[gpu] polarised biorthogonal scf with equal channels vs the unpolarised loop")
+    out = []
+    for ww in (w, wp):
+        op = tc.from_workload(ww, precision=tc.TC_PREC_FP64)
+        hist, n = op.scf(max_iter=5, pmax=2, etol=1e-300, otol=0.0)
+        out.append(np.array(hist[:n]))
+        op.close()
+    _say(f"    energies {out[0]} vs {out[1]}")
+    assert len(out[0]) == len(out[1])
+    np.testing.assert_allclose(out[1], out[0], rtol=1e-10)

@@ -1,6 +1,7 @@
 """The oracle gradient (autograd of the discrete energy) against central finite differences, h = 1e-5."""
 import numpy as np
 import pytest
+import torch
 
 import tcinputs as T
 from oracle import grad as OG
@@ -125,5 +126,59 @@ def test_equal_channels_share_the_unpolarized_gradient():
     for a, b, c in zip(gu, gd, g0):
         np.testing.assert_allclose(a + b, c, rtol=0, atol=1e-12 * np.abs(c).max())
         np.testing.assert_allclose(a, b, rtol=0, atol=1e-12 * np.abs(c).max())
+    np.testing.assert_allclose(gA, gA0, rtol=1e-12)
+    np.testing.assert_allclose(gC, gC0, rtol=1e-12)
+
+
+@pytest.fixture(scope="module")
+def bitc_pol_case():
+    w = T.polarized(T.tiny_fcc(kmesh=(2, 1, 1), grid=8, ecut=2.0, nb=2, a=6.0, occ=[1.0, 0.6], left_mix=0.15,
+                               seed_offset=7), 43, occ_dn=[0.9, 0.3])
+    pairs = OG.bitc_pair_polarized(w)
+    return w, pairs, OG.energy_and_grad_bitc_polarized(w, *pairs)
+
+
+def _energy_bitc_pol(w, ru, lu, rd, ld):
+    from oracle.fftroute import CD, Problem
+
+    with torch.no_grad():
+        t = lambda x: [torch.as_tensor(c, dtype=CD) for c in x]
+        return float(Problem(w, coeff=t(ru), left=t(lu), coeff_dn=t(rd), left_dn=t(ld),
+                             biorthogonalize=False).energy())
+
+
+@pytest.mark.parametrize("which", [0, 1, 2, 3], ids=["right_up", "left_up", "right_dn", "left_dn"])
+def test_bitc_polarized_gradients_match_central_differences(bitc_pol_case, which):
+    """Each of the four partial gradients of the spin-polarised biorthogonal energy (pairs held fixed)
+    against central differences along random directions."""
+    w, pairs, res = bitc_pol_case
+    g = res[1 + which]
+    rng = np.random.default_rng(50 + which)
+    h = 1e-5
+    d = [rng.standard_normal(c.shape) + 1j * rng.standard_normal(c.shape) for c in pairs[which]]
+    e = []
+    for sgn in (1, -1):
+        p = [list(x) for x in pairs]
+        p[which] = [c + sgn * h * x for c, x in zip(pairs[which], d)]
+        e.append(_energy_bitc_pol(w, *p))
+    fd = (e[0] - e[1]) / (2 * h)
+    an = sum(np.sum((np.conj(a) * x).real) for a, x in zip(g, d))
+    assert an == pytest.approx(fd, rel=1e-6, abs=1e-9)
+
+
+def test_bitc_polarized_equal_channels_share_the_unpolarized_gradients():
+    """Two identical biorthogonal channels: each channel's right and left gradients are half of the
+    unpolarised ones (whose pair both spins share); E, dA and dC are the same."""
+    w = T.tiny_fcc(kmesh=(2, 1, 1), grid=8, ecut=2.0, nb=2, a=6.0, occ=[1.0, 0.6], left_mix=0.15, seed_offset=7)
+    r, l = OG.bitc_pair(w)
+    E0, gr0, gl0, gA0, gC0 = OG.energy_and_grad_bitc(w, r, l)
+    wp = w.replace(right_dn=[c.copy() for c in w.right], left_dn=[c.copy() for c in w.left],
+                   occ_dn=[o.copy() for o in w.occ])
+    E, gru, glu, grd, gld, gA, gC = OG.energy_and_grad_bitc_polarized(wp, r, l, r, l)
+    assert E == pytest.approx(E0, rel=1e-13)
+    for up, dn, ref in ((gru, grd, gr0), (glu, gld, gl0)):
+        for a, b, c in zip(up, dn, ref):
+            np.testing.assert_allclose(a + b, c, rtol=0, atol=1e-12 * np.abs(c).max())
+            np.testing.assert_allclose(a, b, rtol=0, atol=1e-12 * np.abs(c).max())
     np.testing.assert_allclose(gA, gA0, rtol=1e-12)
     np.testing.assert_allclose(gC, gC0, rtol=1e-12)
