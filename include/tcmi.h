@@ -136,8 +136,11 @@ int tc_set_kmesh(tc_ctx* ctx, int n1, int n2, int n3);
 int tc_set_grid(tc_ctx* ctx, int N1, int N2, int N3);
 
 /* Plane-wave set of k-point ik: npw Miller triples (m1,m2,m3) (int32, [npw][3]).
- * TC_ERR_GRID if a triple does not fit the grid (|m_i| >= N/2); the grid should
- * also satisfy N/2 >= 2 max|m_i| + 1 for alias-free pair densities (not checked). */
+ * TC_ERR_GRID if a triple does not fit the grid (|m_i| >= N/2); TC_ERR_ARG if a triple
+ * appears twice.  The grid should also satisfy N/2 >= 2 max|m_i| + 1 for alias-free pair
+ * densities (not checked).  This and the other calls that only describe the problem
+ * (cell, k-mesh, grid, Jastrow, options, spin channels, symmetry, band k-points, batch,
+ * memory budget, profiling) do no device work. */
 int tc_set_basis(tc_ctx* ctx, int ik, int npw, const int32_t* miller);
 
 /* Jastrow parameters of Eq. Jastrow: index 0 = parallel spins, 1 = antiparallel.

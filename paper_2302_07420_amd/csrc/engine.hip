@@ -2657,11 +2657,13 @@ template <typename R>
 Engine* make_engine_r(int N, bool zmfma = false) {
   switch (N) {
     case 8: return new_engine<R, 8>(zmfma);
+#ifndef TCMI_HOST_CHECK_BUILD   // the host sanitizer build of the tests compiles the 8-point engine only
     case 12: return new_engine<R, 12>(zmfma);
     case 16: return new_engine<R, 16>(zmfma);
     case 24: return new_engine<R, 24>(zmfma);
     case 32: return new_engine<R, 32>(zmfma);
     case 48: return new_engine<R, 48>(zmfma);
+#endif
     default: return nullptr;
   }
 }
@@ -2777,6 +2779,23 @@ int guard(tc_ctx* c, F&& f) {
     c->err.clear();
     TC_HIP(hipSetDevice(c->device));
     AllocScope as(c->cur_alloc);
+    return f();
+  } catch (const TcError& e) {
+    return fail(c, e.code, e.msg);
+  } catch (const std::bad_alloc&) {
+    return fail(c, TC_ERR_OOM, "host allocation failed");
+  } catch (const std::exception& e) {
+    return fail(c, TC_ERR_DEVICE, e.what());
+  }
+}
+
+// Entry points that only describe the problem (no device work): the same error handling, no device
+// selection, so that they also run where no device is present (the host sanitizer build of the tests).
+template <class F>
+int guard_host(tc_ctx* c, F&& f) {
+  if (!c) return TC_ERR_ARG;
+  try {
+    c->err.clear();
     return f();
   } catch (const TcError& e) {
     return fail(c, e.code, e.msg);
@@ -4098,7 +4117,7 @@ void tc_destroy(tc_ctx* c) {
 const char* tc_last_error(const tc_ctx* c) { return c ? c->err.c_str() : "null context"; }
 
 int tc_set_cell(tc_ctx* c, const double lat[9]) {
-  return guard(c, [&]() -> int {
+  return guard_host(c, [&]() -> int {
     if (!lat) return fail(c, TC_ERR_ARG, "null lattice");
     Problem& pb = c->pb;
     const double* a = lat;
@@ -4125,7 +4144,7 @@ int tc_set_cell(tc_ctx* c, const double lat[9]) {
 }
 
 int tc_set_kmesh(tc_ctx* c, int n1, int n2, int n3) {
-  return guard(c, [&]() -> int {
+  return guard_host(c, [&]() -> int {
     if (n1 < 1 || n2 < 1 || n3 < 1 || n1 > 16 || n2 > 16 || n3 > 16) return fail(c, TC_ERR_KMESH, "k-mesh out of range");
     Problem& pb = c->pb;
     pb.n1 = n1;
@@ -4148,7 +4167,7 @@ int tc_set_kmesh(tc_ctx* c, int n1, int n2, int n3) {
 }
 
 int tc_set_grid(tc_ctx* c, int N1, int N2, int N3) {
-  return guard(c, [&]() -> int {
+  return guard_host(c, [&]() -> int {
     if (N1 != N2 || N2 != N3 || !grid_supported(N1))
       return fail(c, TC_ERR_UNSUPPORTED, "only cubic grids N^3 with N in {8,12,16,24,32,48} are built");
     c->pb.N = N1;
@@ -4160,13 +4179,20 @@ int tc_set_grid(tc_ctx* c, int N1, int N2, int N3) {
 }
 
 int tc_set_basis(tc_ctx* c, int ik, int npw, const int32_t* miller) {
-  return guard(c, [&]() -> int {
+  return guard_host(c, [&]() -> int {
     Problem& pb = c->pb;
     if (pb.nk == 0 || pb.N == 0) return fail(c, TC_ERR_STATE, "set the k-mesh and grid first");
     if (ik < 0 || ik >= pb.nk || npw <= 0 || !miller) return fail(c, TC_ERR_ARG, "bad basis arguments");
     for (int g = 0; g < 3 * npw; ++g)
       if (miller[g] >= pb.N / 2 || miller[g] < -(pb.N / 2) + 1)
         return fail(c, TC_ERR_GRID, "plane wave outside the FFT grid");
+    std::vector<char> seen(size_t(pb.N) * pb.N * pb.N, 0);   // two coefficients on one grid point
+    for (int g = 0; g < npw; ++g) {
+      size_t idx = 0;
+      for (int d = 0; d < 3; ++d) idx = idx * pb.N + size_t((miller[3 * g + d] + pb.N) % pb.N);
+      if (seen[idx]) return fail(c, TC_ERR_ARG, "plane wave listed twice in the basis");
+      seen[idx] = 1;
+    }
     pb.miller[ik].assign(miller, miller + 3 * npw);
     pb.npw[ik] = npw;
     pb.loaded[ik] = 0;
@@ -4177,7 +4203,7 @@ int tc_set_basis(tc_ctx* c, int ik, int npw, const int32_t* miller) {
 }
 
 int tc_set_jastrow(tc_ctx* c, const double A[2], const double C[2]) {
-  return guard(c, [&]() -> int {
+  return guard_host(c, [&]() -> int {
     if (!A || !C) return fail(c, TC_ERR_ARG, "null Jastrow parameters");
     for (int i = 0; i < 2; ++i)
       if (!(A[i] >= 0.0) || !(C[i] > 0.0)) return fail(c, TC_ERR_ARG, "need A >= 0 and C > 0");
@@ -4193,7 +4219,7 @@ int tc_set_jastrow(tc_ctx* c, const double A[2], const double C[2]) {
 }
 
 int tc_set_options(tc_ctx* c, int precision, double alpha, int div_correction, uint64_t term_mask) {
-  return guard(c, [&]() -> int {
+  return guard_host(c, [&]() -> int {
     if (precision != TC_PREC_FP64 && precision != TC_PREC_FP32 && precision != TC_PREC_FP32_SPLITBF16)
       return fail(c, TC_ERR_ARG, "unknown precision");
     if (!(alpha > 0.0)) return fail(c, TC_ERR_ARG, "alpha must be > 0");
@@ -4245,7 +4271,7 @@ int tc_load_orbitals(tc_ctx* c, int ik, int nband, const double* right, const do
 }
 
 int tc_set_nspin(tc_ctx* c, int nspin) {
-  return guard(c, [&]() -> int {
+  return guard_host(c, [&]() -> int {
     if (nspin != 1 && nspin != 2) return fail(c, TC_ERR_ARG, "nspin must be 1 or 2");
     Problem& pb = c->pb;
     if (pb.nk == 0) return fail(c, TC_ERR_STATE, "set the k-mesh before the number of spin channels");
@@ -4261,11 +4287,11 @@ int tc_set_nspin(tc_ctx* c, int nspin) {
 }
 
 int tc_set_band_kpoints(tc_ctx* c, int nkb, const double* kfrac) {
-  return guard(c, [&]() -> int { return set_band_kpoints(c, nkb, kfrac); });
+  return guard_host(c, [&]() -> int { return set_band_kpoints(c, nkb, kfrac); });
 }
 
 int tc_set_band_basis(tc_ctx* c, int ib, int npw, const int32_t* miller) {
-  return guard(c, [&]() -> int { return set_band_basis(c, ib, npw, miller); });
+  return guard_host(c, [&]() -> int { return set_band_basis(c, ib, npw, miller); });
 }
 
 int tc_load_band_orbitals(tc_ctx* c, int ib, int nband, const double* coef, const double* occ) {
@@ -4277,7 +4303,7 @@ int tc_apply_band(tc_ctx* c, double* out, double* eps) {
 }
 
 int tc_set_symmetry(tc_ctx* c, int nsym, const int32_t* rot, const double* tau) {
-  return guard(c, [&]() -> int { return set_symmetry(c, nsym, rot, tau); });
+  return guard_host(c, [&]() -> int { return set_symmetry(c, nsym, rot, tau); });
 }
 
 int tc_load_orbitals_spin(tc_ctx* c, int spin, int ik, int nband, const double* right, const double* left,
@@ -4466,7 +4492,7 @@ int tc_sync(tc_ctx* c) {
 }
 
 int tc_set_batch(tc_ctx* c, int targets_per_batch) {
-  return guard(c, [&]() -> int {
+  return guard_host(c, [&]() -> int {
     if (targets_per_batch < 0) return fail(c, TC_ERR_ARG, "batch must be >= 0");
     c->pb.batch = targets_per_batch;
     c->have_result = false;
@@ -4501,7 +4527,7 @@ int tc_set_allocator(tc_ctx* c, void* (*alloc_fn)(size_t, void*), void (*free_fn
 }
 
 int tc_set_memory_budget(tc_ctx* c, size_t bytes) {
-  return guard(c, [&]() -> int {
+  return guard_host(c, [&]() -> int {
     c->pb.mem_budget = bytes;
     return TC_OK;
   });
@@ -4510,7 +4536,7 @@ int tc_set_memory_budget(tc_ctx* c, size_t bytes) {
 void* tc_get_stream(const tc_ctx* c) { return c ? reinterpret_cast<void*>(c->stream) : nullptr; }
 
 int tc_set_profiling(tc_ctx* c, int on) {
-  return guard(c, [&]() -> int {
+  return guard_host(c, [&]() -> int {
     c->prof.on = on != 0;
     return TC_OK;
   });
