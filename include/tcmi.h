@@ -133,6 +133,16 @@ int tc_set_kmesh(tc_ctx* ctx, int n1, int n2, int n3);
 
 /* FFT grid.  The library supports cubic grids N1 = N2 = N3 = N with
  * N in {8, 12, 16, 24, 32, 48}; anything else is TC_ERR_UNSUPPORTED. */
+/* Monkhorst-Pack shift of the k-mesh (Sec. "Functionalities" of the TC++ description: meshes with or
+ * without a shift): k-point (i1, i2, i3) becomes ((i + s) / n) in units of the reciprocal rows, shift s in
+ * mesh units, each component in [0, 1) (0: Gamma-centred, the default; 1/2: the shift of an even mesh).
+ * Pair shifts k - q and the Gygi-Baldereschi constant do not change; the kinetic energy, the gradient
+ * fields and band corrections use the shifted points.  Call after tc_set_kmesh (which resets it to 0) and
+ * before the plane-wave sets (built by the caller for the shifted points); it discards loaded orbitals and
+ * symmetry.  TC_ERR_STATE before the k-mesh, TC_ERR_ARG for a null or out-of-range shift.  Symmetry
+ * operations must map the shifted mesh onto itself (TC_ERR_ARG from tc_set_symmetry otherwise). */
+int tc_set_kmesh_shift(tc_ctx* ctx, const double shift[3]);
+
 int tc_set_grid(tc_ctx* ctx, int N1, int N2, int N3);
 
 /* Plane-wave set of k-point ik: npw Miller triples (m1,m2,m3) (int32, [npw][3]).
@@ -147,6 +157,11 @@ int tc_set_basis(tc_ctx* ctx, int ik, int npw, const int32_t* miller);
  * A >= 0 (A = 0 gives Hartree-Fock), C > 0.  The cusp relation of Eq. cusp is
  * the caller's choice (A and C are independent here). */
 int tc_set_jastrow(tc_ctx* ctx, const double A[2], const double C[2]);
+
+/* tc_set_jastrow with C from the cusp conditions of Eq. cusp: C_par = sqrt(2 A_par), C_anti = sqrt(A_anti).
+ * A > 0 (TC_ERR_ARG otherwise).  The gradients (tc_energy_backward*) stay the partial derivatives with the
+ * four parameters independent; along the cusp-tied line dE/dA_s + dE/dC_s dC_s/dA_s is the total one. */
+int tc_set_jastrow_cusp(tc_ctx* ctx, const double A[2]);
 
 /* precision: TC_PREC_FP64, TC_PREC_FP32 or TC_PREC_FP32_SPLITBF16 (FFT butterflies,
  * pair products and kernel multiplies in that precision; corrections, overlaps,

@@ -57,7 +57,8 @@ class Brute:
         self.B = 2.0 * math.pi * np.linalg.inv(lat).T
         n1, n2, n3 = w.kmesh
         self.nk = n1 * n2 * n3
-        self.kfrac = np.array([(i1 / n1, i2 / n2, i3 / n3) for i1 in range(n1)
+        s1, s2, s3 = (float(x) for x in getattr(w, "kshift", (0.0, 0.0, 0.0)))   # Monkhorst-Pack shift
+        self.kfrac = np.array([((i1 + s1) / n1, (i2 + s2) / n2, (i3 + s3) / n3) for i1 in range(n1)
                                for i2 in range(n2) for i3 in range(n3)])
         self.grid = tuple(w.grid)
         N1, N2, N3 = self.grid

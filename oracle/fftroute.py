@@ -134,7 +134,10 @@ class Problem:
         self.kmesh = tuple(w.kmesh)
         self.nk = int(np.prod(self.kmesh))
         n1, n2, n3 = self.kmesh
-        self.kfrac = np.array([(i1 / n1, i2 / n2, i3 / n3) for i1 in range(n1)
+        # Monkhorst-Pack mesh with or without a shift s (mesh units): k = (i + s) / n
+        self.kshift = np.asarray(getattr(w, "kshift", (0.0, 0.0, 0.0)), dtype=np.float64)
+        s1, s2, s3 = self.kshift
+        self.kfrac = np.array([((i1 + s1) / n1, (i2 + s2) / n2, (i3 + s3) / n3) for i1 in range(n1)
                                for i2 in range(n2) for i3 in range(n3)])
         # band (zero-weight) k-points off the mesh (Sec. 2.5, band-structure calculation): their
         # orbitals are targets of every term and partners of none; their fillings enter only the
@@ -304,7 +307,8 @@ class Problem:
         """Gygi-Baldereschi constant of Eq. correction2 with A_aux = exp(-alpha q^2)/q^2.
 
         Sigma_aux = sum over the mesh q and all G (ball exp(-alpha|k-q+G|^2) > 1e-18) of
-        A_aux(k-q+G), excluding k-q+G = 0; uniform mesh so k = 0 is used.  Also
+        A_aux(k-q+G), excluding k-q+G = 0; k and q both on the mesh, so k - q runs over the unshifted
+        mesh whatever its shift, and k = 0 with the unshifted points is used.  Also
         returns the vector sum of Eq. correction_nabla (zero on a uniform mesh).
         """
         a = self.alpha
@@ -315,7 +319,7 @@ class Problem:
         M = np.stack(np.meshgrid(*rr, indexing="ij"), -1).reshape(-1, 3).astype(np.float64)
         tot = 0.0
         vec = np.zeros(3)
-        for q in self.kfrac:
+        for q in self.kfrac - (self.kshift / np.asarray(self.kmesh, dtype=np.float64))[None, :]:
             Q = (M - q[None, :]) @ self.B
             q2 = np.sum(Q * Q, 1)
             ok = (q2 > 1e-20) & (a * q2 < 41.45)

@@ -82,7 +82,9 @@ def heg_terms(w, A=None, C=None, alpha=None, div_correction=True, reading="print
     omega = abs(np.linalg.det(lat))
     nk = int(np.prod(w.kmesh))
     n1, n2, n3 = w.kmesh
-    kf = [np.array([i1 / n1, i2 / n2, i3 / n3]) for i1 in range(n1) for i2 in range(n2) for i3 in range(n3)]
+    s1, s2, s3 = (float(x) for x in getattr(w, "kshift", (0.0, 0.0, 0.0)))   # Monkhorst-Pack shift
+    kf = [np.array([(i1 + s1) / n1, (i2 + s2) / n2, (i3 + s3) / n3])
+          for i1 in range(n1) for i2 in range(n2) for i3 in range(n3)]
     A = np.asarray(w.A if A is None else A, dtype=np.float64)
     C = np.asarray(w.C if C is None else C, dtype=np.float64)
     alpha = w.alpha if alpha is None else alpha

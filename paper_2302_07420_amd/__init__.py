@@ -71,6 +71,8 @@ def lib():
         "tc_last_error": (ctypes.c_char_p, [P]),
         "tc_set_cell": (I, [P, dp]),
         "tc_set_kmesh": (I, [P, I, I, I]),
+        "tc_set_kmesh_shift": (I, [P, dp]),
+        "tc_set_jastrow_cusp": (I, [P, dp]),
         "tc_set_grid": (I, [P, I, I, I]),
         "tc_set_basis": (I, [P, I, I, ctypes.POINTER(ctypes.c_int32)]),
         "tc_set_jastrow": (I, [P, dp, dp]),
@@ -182,9 +184,22 @@ class TCOperator:
         a = np.ascontiguousarray(np.asarray(lattice, dtype=np.float64).reshape(9))
         self._check(self._L.tc_set_cell(self._h, _dp(a)), "tc_set_cell")
 
-    def set_kmesh(self, n1, n2, n3):
+    def set_kmesh(self, n1, n2, n3, shift=None):
+        """n1 x n2 x n3 Monkhorst-Pack mesh; ``shift`` (3 components in [0, 1), mesh units) moves every
+        k-point to (i + s) / n (tc_set_kmesh_shift)."""
         self._check(self._L.tc_set_kmesh(self._h, n1, n2, n3), "tc_set_kmesh")
         self.npw = [0] * (n1 * n2 * n3)
+        if shift is not None and any(float(x) != 0.0 for x in shift):
+            self.set_kmesh_shift(shift)
+
+    def set_kmesh_shift(self, shift):
+        s = np.ascontiguousarray(np.asarray(shift, dtype=np.float64).reshape(3))
+        self._check(self._L.tc_set_kmesh_shift(self._h, _dp(s)), "tc_set_kmesh_shift")
+
+    def set_jastrow_cusp(self, A):
+        """A (parallel, antiparallel) with C from the cusp conditions (tc_set_jastrow_cusp)."""
+        a = np.ascontiguousarray(np.asarray(A, dtype=np.float64).reshape(2))
+        self._check(self._L.tc_set_jastrow_cusp(self._h, _dp(a)), "tc_set_jastrow_cusp")
 
     def set_grid(self, N1, N2, N3):
         self._check(self._L.tc_set_grid(self._h, N1, N2, N3), "tc_set_grid")
@@ -450,7 +465,7 @@ def from_workload(w, precision=TC_PREC_FP64, terms=TERM_ALL, div_correction=True
     if not pair_store:
         op.set_pair_store(False)
     op.set_cell(w.lattice)
-    op.set_kmesh(*w.kmesh)
+    op.set_kmesh(*w.kmesh, shift=getattr(w, "kshift", None))
     op.set_grid(*w.grid)
     for ik, m in enumerate(w.miller):
         op.set_basis(ik, m)

@@ -171,6 +171,7 @@ struct Problem {
   bool bitc = false;                      // every k-point has left orbitals (set by prepare)
   bool negate_b = false;                  // grad-u . grad terms with sign -1 (the adjoint operator)
   int nspin = 1;                          // 2: spin-polarised, the down channel's own orbitals
+  double kshift[3] = {0, 0, 0};           // Monkhorst-Pack shift of the k-mesh (mesh units)
   std::vector<double> occ_dn;             // [nk][nb] fillings of the down channel (nspin = 2)
   std::vector<char> loaded_dn;            // per k (nspin = 2)
   std::vector<char> left_dn;              // per k: the down channel loaded with left orbitals
@@ -198,7 +199,15 @@ struct Problem {
 
   int P() const { return nk * nb; }
   long NR() const { return long(N) * N * N; }
+  // k-point ik of the Monkhorst-Pack mesh: (i + s) / n per axis (s = kshift, mesh units)
   void kfrac(int ik, double* f) const {
+    kfrac_mesh(ik, f);
+    f[0] += kshift[0] / n1;
+    f[1] += kshift[1] / n2;
+    f[2] += kshift[2] / n3;
+  }
+  // the same without the shift: differences of mesh k-points (k - q) run over these
+  void kfrac_mesh(int ik, double* f) const {
     const int i3 = ik % n3, i2 = (ik / n3) % n2, i1 = ik / (n3 * n2);
     f[0] = double(i1) / n1;
     f[1] = double(i2) / n2;
@@ -209,7 +218,8 @@ struct Problem {
 inline int mfreq_h(int i, int N) { return i < N / 2 ? i : i - N; }
 
 // Gygi-Baldereschi bracket of Eq. correction2 with A_aux = e^{-alpha q^2}/q^2 (Eq. aux),
-// summed over the mesh and the ball exp(-alpha |k-q+G|^2) > 1e-18 (uniform mesh: k = 0).
+// summed over the mesh and the ball exp(-alpha |k-q+G|^2) > 1e-18.  k and q are both mesh points, so
+// k - q runs over the unshifted mesh whatever the shift: k = 0 and the unshifted points are used.
 void gb_constant(Problem& pb) {
   const double a = pb.alpha;
   const double qmax = std::sqrt(41.45 / a);
@@ -222,7 +232,7 @@ void gb_constant(Problem& pb) {
   double sum = 0, comp = 0;   // Neumaier summation
   for (int ik = 0; ik < pb.nk; ++ik) {
     double f[3];
-    pb.kfrac(ik, f);
+    pb.kfrac_mesh(ik, f);
     for (int m1 = -mm[0]; m1 <= mm[0]; ++m1)
       for (int m2 = -mm[1]; m2 <= mm[1]; ++m2)
         for (int m3 = -mm[2]; m3 <= mm[2]; ++m3) {
@@ -3191,7 +3201,7 @@ bool sym_map_k(const Problem& pb, const int* R, int k, int* kout, int* b) {
   int idx[3];
   for (int i = 0; i < 3; ++i) {
     g[i] = R[i] * f[0] + R[3 + i] * f[1] + R[6 + i] * f[2];   // (R^T f)_i
-    const double x = g[i] * n[i];
+    const double x = g[i] * n[i] - pb.kshift[i];                 // mesh index of the image (shifted mesh)
     const double xr = std::round(x);
     if (std::fabs(x - xr) > 1e-9) return false;
     const int t = int(xr);
@@ -4151,6 +4161,7 @@ int tc_set_kmesh(tc_ctx* c, int n1, int n2, int n3) {
     pb.n2 = n2;
     pb.n3 = n3;
     pb.nk = n1 * n2 * n3;
+    pb.kshift[0] = pb.kshift[1] = pb.kshift[2] = 0.0;
     pb.miller.assign(pb.nk, {});
     pb.npw.assign(pb.nk, 0);
     pb.loaded.assign(pb.nk, 0);
@@ -4211,6 +4222,44 @@ int tc_set_jastrow(tc_ctx* c, const double A[2], const double C[2]) {
       c->pb.A[i] = A[i];
       c->pb.C[i] = C[i];
     }
+    c->pb.jastrow = true;
+    c->tables_dirty = true;
+    c->have_result = false;
+    return TC_OK;
+  });
+}
+
+int tc_set_kmesh_shift(tc_ctx* c, const double shift[3]) {
+  return guard_host(c, [&]() -> int {
+    Problem& pb = c->pb;
+    if (pb.nk == 0) return fail(c, TC_ERR_STATE, "set the k-mesh before its shift");
+    if (!shift) return fail(c, TC_ERR_ARG, "null shift");
+    for (int i = 0; i < 3; ++i)
+      if (!(shift[i] >= 0.0 && shift[i] < 1.0)) return fail(c, TC_ERR_ARG, "shift components must lie in [0, 1)");
+    for (int i = 0; i < 3; ++i) pb.kshift[i] = shift[i];
+    // the k-points moved: orbitals and symmetry are set again (the plane-wave sets are the caller's)
+    std::fill(pb.loaded.begin(), pb.loaded.end(), 0);
+    std::fill(pb.left.begin(), pb.left.end(), 0);
+    std::fill(pb.loaded_dn.begin(), pb.loaded_dn.end(), 0);
+    std::fill(pb.left_dn.begin(), pb.left_dn.end(), 0);
+    pb.nsym = 0;
+    pb.sym_ready = false;
+    c->tables_dirty = true;
+    c->have_result = false;
+    return TC_OK;
+  });
+}
+
+int tc_set_jastrow_cusp(tc_ctx* c, const double A[2]) {
+  return guard_host(c, [&]() -> int {
+    if (!A) return fail(c, TC_ERR_ARG, "null Jastrow parameters");
+    for (int i = 0; i < 2; ++i)
+      if (!(A[i] > 0.0)) return fail(c, TC_ERR_ARG, "the cusp conditions need A > 0");
+    // Eq. cusp: C = sqrt(2 A) for parallel spins, sqrt(A) for antiparallel ones
+    c->pb.A[0] = A[0];
+    c->pb.A[1] = A[1];
+    c->pb.C[0] = std::sqrt(2.0 * A[0]);
+    c->pb.C[1] = std::sqrt(A[1]);
     c->pb.jastrow = true;
     c->tables_dirty = true;
     c->have_result = false;

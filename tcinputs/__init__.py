@@ -39,12 +39,15 @@ def reciprocal(lattice: np.ndarray) -> np.ndarray:
     return 2.0 * math.pi * np.linalg.inv(np.asarray(lattice, dtype=np.float64)).T
 
 
-def kmesh_fractions(n1: int, n2: int, n3: int) -> np.ndarray:
+def kmesh_fractions(n1: int, n2: int, n3: int, shift=(0.0, 0.0, 0.0)) -> np.ndarray:
+    """Fractional k-points (i + s) / n of an n1 x n2 x n3 Monkhorst-Pack mesh, shift s in mesh units
+    (0: Gamma-centred)."""
+    s1, s2, s3 = (float(x) for x in shift)
     out = []
     for i1 in range(n1):
         for i2 in range(n2):
             for i3 in range(n3):
-                out.append((i1 / n1, i2 / n2, i3 / n3))
+                out.append(((i1 + s1) / n1, (i2 + s2) / n2, (i3 + s3) / n3))
     return np.array(out, dtype=np.float64)
 
 
@@ -102,6 +105,8 @@ class Workload:
     band_miller: Optional[List[np.ndarray]] = None
     band_right: Optional[List[np.ndarray]] = None
     band_occ: Optional[List[np.ndarray]] = None
+    # shift of the k-mesh in mesh units (0: Gamma-centred; 1/2: the Monkhorst-Pack shift of an even mesh)
+    kshift: tuple = (0.0, 0.0, 0.0)
 
     @property
     def omega(self) -> float:
@@ -113,7 +118,7 @@ class Workload:
 
     @property
     def kfrac(self) -> np.ndarray:
-        return kmesh_fractions(*self.kmesh)
+        return kmesh_fractions(*self.kmesh, shift=self.kshift)
 
     @property
     def nband(self) -> int:
@@ -149,11 +154,11 @@ def _orthonormal_random(rng, npw, nb, envelope):
     return np.ascontiguousarray(q.T)
 
 
-def random_orbitals(lattice, kmesh, ecut, nb, sigma, seed, left_mix=None):
+def random_orbitals(lattice, kmesh, ecut, nb, sigma, seed, left_mix=None, kshift=(0.0, 0.0, 0.0)):
     B = reciprocal(lattice)
     rng = np.random.Generator(np.random.PCG64(seed))
     mill, right, left = [], [], []
-    for kf in kmesh_fractions(*kmesh):
+    for kf in kmesh_fractions(*kmesh, shift=kshift):
         M = miller_sphere(lattice, kf, ecut)
         G = M @ B
         env = np.exp(-np.sum(G * G, axis=1) / (2.0 * sigma * sigma))
@@ -407,14 +412,15 @@ def heg_gamma(rs=4.0, nelec=14, grid=16, mmax2=9, occ_m2=1) -> Workload:
                     [np.ones(nb)], (A, A), cusp_C(A), 10.0 / kc ** 2, nelec)
 
 
-def heg_twist(rs=2.0, nelec=54, tw=2, grid=32, ecut=None, nocc=27) -> Workload:
-    """Electron gas on a tw^3 twist grid; nocc lowest |k+G|^2 plane waves per twist."""
+def heg_twist(rs=2.0, nelec=54, tw=2, grid=32, ecut=None, nocc=27, kshift=(0.0, 0.0, 0.0)) -> Workload:
+    """Electron gas on a tw^3 twist grid (shifted by ``kshift`` mesh units); nocc lowest |k+G|^2 plane waves
+    per twist."""
     L = (nelec * 4.0 * math.pi / 3.0 * rs ** 3) ** (1.0 / 3.0)
     lat = sc_lattice(L)
     if ecut is None:
         ecut = 5.78
     mill, right = [], []
-    for kf in kmesh_fractions(tw, tw, tw):
+    for kf in kmesh_fractions(tw, tw, tw, shift=kshift):
         M = miller_sphere(lat, kf, ecut)             # sorted by |k+G|^2 then m
         coef = np.zeros((nocc, M.shape[0]), dtype=np.complex128)
         coef[np.arange(nocc), np.arange(nocc)] = 1.0
@@ -423,25 +429,28 @@ def heg_twist(rs=2.0, nelec=54, tw=2, grid=32, ecut=None, nocc=27) -> Workload:
     A = rpa_A(L ** 3, nelec)
     kc = math.sqrt(2.0 * ecut)
     return Workload(f"heg{nelec}_twist{tw}", lat, (tw,) * 3, (grid,) * 3, mill, right, None,
-                    [np.ones(nocc) for _ in mill], (A, A), cusp_C(A), 10.0 / kc ** 2, nelec)
+                    [np.ones(nocc) for _ in mill], (A, A), cusp_C(A), 10.0 / kc ** 2, nelec,
+                    kshift=tuple(float(x) for x in kshift))
 
 
 def fcc_si(kmesh=(4, 4, 4), grid=24, ecut=8.14, nb=4, a=10.26, supercell=1,
-           seed_offset=2, left_mix=None, occ=None) -> Workload:
-    """Diamond-lattice silicon-like cell with random smooth orthonormal orbitals."""
+           seed_offset=2, left_mix=None, occ=None, kshift=(0.0, 0.0, 0.0)) -> Workload:
+    """Diamond-lattice silicon-like cell with random smooth orthonormal orbitals (k-mesh shifted by
+    ``kshift`` mesh units)."""
     lat = fcc_lattice(a) * supercell
     nelec = 8 * supercell ** 3
     omega = abs(np.linalg.det(lat))
     sigma = 3.0 * 2.0 * math.pi / a
     mill, right, left = random_orbitals(lat, kmesh, ecut, nb, sigma,
-                                        SEED_BASE + seed_offset, left_mix)
+                                        SEED_BASE + seed_offset, left_mix, kshift)
     A = rpa_A(omega, nelec)
     kc = math.sqrt(2.0 * ecut)
     nk = int(np.prod(kmesh))
     occs = [np.ones(nb) if occ is None else np.asarray(occ, dtype=np.float64) for _ in range(nk)]
     return Workload(f"fcc_si_x{supercell}_k{'x'.join(map(str, kmesh))}_g{grid}",
                     lat, tuple(kmesh), (grid,) * 3 if np.isscalar(grid) else tuple(grid),
-                    mill, right, left, occs, (A, A), cusp_C(A), 10.0 / kc ** 2, nelec)
+                    mill, right, left, occs, (A, A), cusp_C(A), 10.0 / kc ** 2, nelec,
+                    kshift=tuple(float(x) for x in kshift))
 
 
 WORKLOADS = {
@@ -480,10 +489,10 @@ def workload(name: str) -> Workload:
 
 
 def tiny_fcc(kmesh=(2, 1, 1), grid=8, ecut=1.2, nb=2, a=6.0, seed_offset=100,
-             left_mix=None, occ=None, A=None, C=None, alpha=None) -> Workload:
+             left_mix=None, occ=None, A=None, C=None, alpha=None, kshift=(0.0, 0.0, 0.0)) -> Workload:
     """A small random problem the oracle finishes in well under a second."""
     w = fcc_si(kmesh=kmesh, grid=grid, ecut=ecut, nb=nb, a=a, seed_offset=seed_offset,
-               left_mix=left_mix, occ=occ)
+               left_mix=left_mix, occ=occ, kshift=kshift)
     repl = {"name": f"tiny_fcc_k{'x'.join(map(str, kmesh))}_g{grid}"}
     if A is not None:
         repl["A"] = tuple(A)

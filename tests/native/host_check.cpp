@@ -102,10 +102,14 @@ int main(int argc, char** argv) {
   code("grid_not_cubic", tc_set_grid(c, 8, 8, 16));
   code("basis_before_mesh", tc_set_basis(c, 0, 1, m_dup));
   code("nspin_before_mesh", tc_set_nspin(c, 2));
+  const double half[3] = {0.5, 0.5, 0.5}, one[3] = {1.0, 0.0, 0.0}, neg[3] = {-0.25, 0.0, 0.0};
+  code("shift_before_mesh", tc_set_kmesh_shift(c, half));
   code("symmetry_before_mesh", tc_set_symmetry(c, 0, nullptr, nullptr));
   code("jastrow_null", tc_set_jastrow(c, nullptr, C));
   code("jastrow_negative_A", tc_set_jastrow(c, bad_a, C));
   code("jastrow_zero_C", tc_set_jastrow(c, A, bad_c));
+  code("cusp_null", tc_set_jastrow_cusp(c, nullptr));
+  code("cusp_negative_A", tc_set_jastrow_cusp(c, bad_a));
   code("options_precision", tc_set_options(c, 7, alpha, TC_DIV_PRINTED, ~0ull));
   code("options_alpha", tc_set_options(c, TC_PREC_FP64, 0.0, TC_DIV_PRINTED, ~0ull));
   code("options_div", tc_set_options(c, TC_PREC_FP64, alpha, 9, ~0ull));
@@ -120,6 +124,23 @@ int main(int argc, char** argv) {
   code("options", tc_set_options(c, TC_PREC_FP64, alpha, TC_DIV_PRINTED, ~0ull));
   code("nspin_3", tc_set_nspin(c, 3));
   code("nspin_2", tc_set_nspin(c, 2));
+  code("shift_null", tc_set_kmesh_shift(c, nullptr));
+  code("shift_one", tc_set_kmesh_shift(c, one));
+  code("shift_negative", tc_set_kmesh_shift(c, neg));
+  code("shift", tc_set_kmesh_shift(c, half));
+  {   // the shifted points and the unchanged mesh differences
+    double f[3], g[3];
+    ctx.pb.kfrac(ctx.pb.nk - 1, f);
+    ctx.pb.kfrac_mesh(ctx.pb.nk - 1, g);
+    for (int i = 0; i < 3; ++i) EXPECT(std::fabs(f[i] - g[i] - 0.5 / km[i]) < 1e-15);
+  }
+  const double sig_before = (gb_constant(ctx.pb), ctx.pb.sigma_aux);
+  code("kmesh_again", tc_set_kmesh(c, km[0], km[1], km[2]));   // resets the shift
+  EXPECT(ctx.pb.kshift[0] == 0.0 && ctx.pb.kshift[1] == 0.0 && ctx.pb.kshift[2] == 0.0);
+  gb_constant(ctx.pb);
+  EXPECT(ctx.pb.sigma_aux == sig_before);   // the Gygi-Baldereschi sum uses mesh differences only
+  code("cusp", tc_set_jastrow_cusp(c, A));
+  EXPECT(ctx.pb.C[0] == std::sqrt(2.0 * A[0]) && ctx.pb.C[1] == std::sqrt(A[1]));
   code("basis_index", tc_set_basis(c, ctx.pb.nk, 1, m_dup));
   code("basis_null", tc_set_basis(c, 0, 1, nullptr));
   code("basis_outside_grid", tc_set_basis(c, 0, 1, m_out));

@@ -39,6 +39,8 @@ CASES = {
                                                        occ=[1.0, 0.8, 0.0], left_mix=0.2, seed_offset=7),
     "fcc_k121_g16_bitc": lambda: T.tiny_fcc(kmesh=(1, 2, 1), grid=16, ecut=3.0, nb=2, a=7.0, left_mix=0.1,
                                             seed_offset=9),
+    "fcc_k211_g8_bitc_shifted": lambda: T.tiny_fcc(kmesh=(2, 1, 1), grid=8, ecut=2.0, nb=2, a=6.0, occ=[1.0, 0.7],
+                                                   left_mix=0.15, kshift=(0.5, 0.5, 0.5)),
 }
 
 

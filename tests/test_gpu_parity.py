@@ -1,4 +1,5 @@
-"""Parity of the HIP path with the FP64 oracle, element by element, through the C ABI."""
+"""Parity of the HIP path with the FP64 oracle, element by element, through the C ABI (one case on a
+shifted Monkhorst-Pack mesh); the cusp-tied Jastrow entry point against explicit C."""
 import numpy as np
 import pytest
 
@@ -50,6 +51,9 @@ CASES = {
     "fcc_k222_g12_empty_band": lambda: T.tiny_fcc(kmesh=(2, 2, 2), grid=12, ecut=2.0, nb=3, a=6.0,
                                                    occ=[1.0, 0.9, 0.0]),
     "fcc_k121_g16_nb1": lambda: T.tiny_fcc(kmesh=(1, 2, 1), grid=16, ecut=3.0, nb=1, a=7.0),
+    # Monkhorst-Pack shifted mesh: k = (i + s) / n
+    "fcc_k221_g12_shifted": lambda: T.tiny_fcc(kmesh=(2, 2, 1), grid=12, ecut=2.0, nb=2, a=6.0, occ=[1.0, 0.8],
+                                               kshift=(0.5, 0.25, 0.0)),
 }
 
 
@@ -243,4 +247,26 @@ def test_readings_differ_and_bad_code_is_rejected():
     op = tc.TCOperator(0)
     with pytest.raises(tc.TCError, match="status -1"):
         op._check(op._L.tc_set_options(op._h, 0, 1.0, 3, tc.TERM_ALL), "tc_set_options")
+    op.close()
+
+
+def test_cusp_tied_jastrow_equals_explicit_c():
+    """tc_set_jastrow_cusp(A) gives the operator of tc_set_jastrow(A, C) with C from Eq. cusp."""
+    w = T.tiny_fcc(kmesh=(2, 1, 1), grid=8, ecut=2.0, nb=2, a=6.0, occ=[1.0, 0.7])
+    A = (0.7, 0.45)
+    C = (np.sqrt(2 * A[0]), np.sqrt(A[1]))
+    _say("[gpu] cusp-tied Jastrow vs explicit C")
+    out = []
+    for tied in (False, True):
+        op = tc.from_workload(w, precision=tc.TC_PREC_FP64, A=A, C=C)
+        if tied:
+            op.set_jastrow_cusp(A)
+        out.append((op.apply(), op.energy()[0]))
+        op.close()
+    assert out[1][1] == out[0][1]
+    for a, b in zip(out[1][0], out[0][0]):
+        np.testing.assert_array_equal(a, b)
+    op = tc.TCOperator()
+    with pytest.raises(tc.TCError, match="status"):
+        op.set_jastrow_cusp((0.0, 1.0))
     op.close()

@@ -36,7 +36,8 @@ EXPECTED = {
     "nspin_2": OK, "basis_index": ARG, "basis_null": ARG, "basis_outside_grid": GRID, "basis_duplicate": ARG,
     "basis": OK, "symmetry_det": ARG, "symmetry_tau": ARG, "symmetry_not_group": ARG, "symmetry": OK,
     "symmetry_off": OK, "band_setter_takes_mesh_point": OK, "band_negative": ARG, "band": OK,
-    "band_basis_index": ARG,
+    "band_basis_index": ARG, "shift_before_mesh": STATE, "cusp_null": ARG, "cusp_negative_A": ARG,
+    "shift_null": ARG, "shift_one": ARG, "shift_negative": ARG, "shift": OK, "kmesh_again": OK, "cusp": OK,
 }
 
 
