@@ -1178,7 +1178,7 @@ struct EngineT : Engine {
   // quarter of the device (at least 16 GiB) free.  With one (tc_set_memory_budget): when the store and
   // a batch of 8 targets fit in it.  Released when it does not fit; never under the no-allocation scratch.
   bool pair_store(const Problem& pb) {
-    const size_t need = size_t(5) * pb.P() * pb.P() * NR;
+    const size_t need = size_t(5) * pb.nspin * pb.P() * pb.P() * NR;   // one region per spin channel
     if (t_arena) return false;
     if (!pb.pair_store) {
       allB.release();
@@ -1307,13 +1307,18 @@ struct EngineT : Engine {
     budget_alloc = budget_bytes;
   }
 
+  // One application of the operator (Sec. 2.6, the six stages above) for one or two spin channels
+  // (Sec. 2.1, Eq. SCF: one orbital set per spin), in TC mode or the biorthogonal mode (the left orbitals
+  // chi as bras), with the orbitals, trial vectors (ts) or band orbitals (ts->band) as targets.  With two
+  // channels the Hartree-type fields of target spin s take the parallel tables on its own density and the
+  // antiparallel ones on the other's, exchange-type terms pair orbitals of one spin, and the occupied pass
+  // keeps the parallel and antiparallel parts of h5 apart: h6 of spin s sums the first over own-spin rows
+  // and the second over other-spin rows.
   void apply(hipStream_t s, Shared& sh, const Problem& pb, double* stage_ms, const TargetSet* ts) override {
-    if (pb.nspin == 2) {   // spin-polarised (TC mode; the orbitals or trial vectors of each channel as targets)
-      apply_pol(s, sh, pb, stage_ms, ts);
-      return;
-    }
     const int P = pb.P();
     const int nb = pb.nb;
+    const int ns = pb.nspin;
+    const bool pol = ns == 2;
     Masks m = make_masks(pb.mask);
     if (pb.negate_b) {   // v2 -> v2^dagger: the grad-u . grad terms change sign (with the ADJOINT tables)
       m.m2bh1 = -m.m2bh1;
@@ -1326,9 +1331,10 @@ struct EngineT : Engine {
     const bool need_B = m.m2bx2 || m.m3b3 || m.m3b4 || m.m3b5;
     // With the orbitals as targets, the pass-A pair (t = b, q = a) has the density conj(psi_a) psi_b and the
     // momentum Delta = k_b - k_a of the occupied pair (a, b), and the four fields of its z stage after V are
-    // the occupied pass's.  When every pair's pass-A z-stage output fits on the device it is computed once,
-    // before the occupied pass, which then reads it in place of its own pair densities and z stage.  (The
-    // store is settled before the batch buffers, which take what it leaves of a caller's budget.)
+    // the occupied pass's.  When every pair's pass-A z-stage output fits on the device (one region per spin
+    // channel) it is computed once, before the occupied pass, which then reads it in place of its own pair
+    // densities and z stage.  (The store is settled before the batch buffers, which take what it leaves of a
+    // caller's budget.)
     const bool keepA = !ts && need_occ && need_A && pair_store(pb);
     ensure(pb, pair_budget(pb));
     // targets: the orbitals, or nbt trial vectors per k-point
@@ -1350,9 +1356,28 @@ struct EngineT : Engine {
       for (int e = 0; e < 3; ++e)
         mm.b[3 * d + e] = R(pb.B[3 * d] * pb.B[3 * e] + pb.B[3 * d + 1] * pb.B[3 * e + 1] + pb.B[3 * d + 2] * pb.B[3 * e + 2]);
     const Tables tb{tV.p, tU1.p, tU2.p, dfr.p};
-    // biorthogonal mode: bras use the left orbitals chi; TC mode: chi = psi (same array)
     const bool bitc = pb.bitc;
-    const cx<R>* X = bitc ? chi.p : psi.p;
+    // per-channel fields (the second of each pair only with two channels); bras: the left orbitals chi in
+    // the biorthogonal mode, psi in TC mode
+    cx<R>* PSI[2] = {psi.p, psi1.p};
+    cx<R>* DD[2] = {D.p, D1.p};
+    cx<R>* DL[2] = {Dl.p, Dl1.p};
+    cx<R>* HL[2] = {Hl.p, Hl1.p};
+    cx<R>* H3[2] = {H3a4.p, H3a4_1.p};
+    cx<R>* NJ[2] = {nJ.p, nJ1.p};
+    cx<R>* LOC[2] = {loc.p, loc1.p};
+    cx<R>* CHI[2] = {chi.p, chi1.p};
+    const cx<R>* XS[2] = {bitc ? chi.p : psi.p, bitc ? chi1.p : psi1.p};
+    R* H5P[2] = {h5.p, h5_1.p};          // real h5 (TC); with two channels its parallel-channel part
+    R* H5A[2] = {h5a0.p, h5a1.p};        // antiparallel-channel part (two channels)
+    cx<R>* H5C[2] = {h5c.p, h5c_1.p};    // the same, complex (biorthogonal mode)
+    cx<R>* H5CA[2] = {h5ca0.p, h5ca1.p};
+    cx<R>* HBC[2] = {H3bc.p, H3bc_1.p};  // conj(H3b), then its lattice components (biorthogonal mode)
+    const double* W[2] = {sh.w.p, sh.w.p + P};
+    const size_t cofs = size_t(2) * P * pb.npw_max;   // doubles per channel of the coefficients
+    const size_t tcofs = size_t(2) * NTG * tnpm;      // doubles per channel of the target coefficients
+    // the resident store of channel c: [P][P][5][N^3] pass-A z-stage outputs, pair-major in target order
+    auto store = [&](int c) { return allB.p + size_t(c) * P * P * 5 * NR; };
     // algorithmic bytes: fields each launch must read or write once (working precision)
     const double fb = double(sizeof(cx<R>)) * NR;
     const double fd = double(sizeof(cx<double>)) * NR;
@@ -1366,182 +1391,285 @@ struct EngineT : Engine {
     std::vector<hipEvent_t> bev;   // per batch: begin A, end A, end B
     ev.rec(0, s);
 
-    // ---- 0: G -> r (psi and the three components of D)
-    TC_HIP(hipMemsetAsync(psi.p, 0, size_t(P) * NR * sizeof(cx<R>), s));
-    TC_HIP(hipMemsetAsync(D.p, 0, size_t(3) * P * NR * sizeof(cx<R>), s));
-    if (bitc) TC_HIP(hipMemsetAsync(chi.p, 0, size_t(P) * NR * sizeof(cx<R>), s));
+    // ---- 0: G -> r (psi, the three components of D, and chi in the biorthogonal mode), per channel
     const unsigned gsc = nblk(long(P) * pb.npw_max);
-    K(TC_K_SCATTER, 0.0, [&] {
-      hipLaunchKernelGGL((k_scatter<R>), dim3(gsc), dim3(256), 0, s, sh.coef.p, sh.boxidx.p, sh.npw.p, sh.kg.p, nb,
-                         pb.npw_max, P, -1, psi.p, NR);
-      for (int c = 0; c < 3; ++c)
-        hipLaunchKernelGGL((k_scatter<R>), dim3(gsc), dim3(256), 0, s, sh.coef.p, sh.boxidx.p, sh.npw.p, sh.kg.p, nb,
-                           pb.npw_max, P, c, D.p + size_t(c) * P * NR, NR);
-      if (bitc)
-        hipLaunchKernelGGL((k_scatter<R>), dim3(gsc), dim3(256), 0, s, sh.coefL.p, sh.boxidx.p, sh.npw.p, sh.kg.p, nb,
-                           pb.npw_max, P, -1, chi.p, NR);
-    });
-    fft3d_t<R, N>(psi.p, P, +1, s, pf);
-    if (bitc) fft3d_t<R, N>(chi.p, P, +1, s, pf);
+    for (int c = 0; c < ns; ++c) {
+      const double* cf = sh.coef.p + c * cofs;
+      TC_HIP(hipMemsetAsync(PSI[c], 0, size_t(P) * NR * sizeof(cx<R>), s));
+      TC_HIP(hipMemsetAsync(DD[c], 0, size_t(3) * P * NR * sizeof(cx<R>), s));
+      if (bitc) TC_HIP(hipMemsetAsync(CHI[c], 0, size_t(P) * NR * sizeof(cx<R>), s));
+      K(TC_K_SCATTER, 0.0, [&] {
+        hipLaunchKernelGGL((k_scatter<R>), dim3(gsc), dim3(256), 0, s, cf, sh.boxidx.p, sh.npw.p, sh.kg.p, nb,
+                           pb.npw_max, P, -1, PSI[c], NR);
+        for (int d = 0; d < 3; ++d)
+          hipLaunchKernelGGL((k_scatter<R>), dim3(gsc), dim3(256), 0, s, cf, sh.boxidx.p, sh.npw.p, sh.kg.p, nb,
+                             pb.npw_max, P, d, DD[c] + size_t(d) * P * NR, NR);
+        if (bitc)
+          hipLaunchKernelGGL((k_scatter<R>), dim3(gsc), dim3(256), 0, s, sh.coefL.p + c * cofs, sh.boxidx.p,
+                             sh.npw.p, sh.kg.p, nb, pb.npw_max, P, -1, CHI[c], NR);
+      });
+      fft3d_t<R, N>(PSI[c], P, +1, s, pf);
+      if (bitc) fft3d_t<R, N>(CHI[c], P, +1, s, pf);
+      fft3d_t<R, N>(DD[c], 3L * P, +1, s, pf);
+      K(TC_K_OTHER, 6.0 * fb * P, [&] {
+        hipLaunchKernelGGL((k_lattice3<R, N>), dim3(nblk(long(P) * NR)), dim3(256), 0, s, DD[c], DL[c], bm, long(P),
+                           NR, long(P) * NR);
+      });
+    }
+    // target fields of trial vectors or band orbitals (channel c's; with one channel made here, with two at
+    // that channel's target passes)
     if (ts) {
       psiT.alloc(size_t(NTG) * NR);
       DT.alloc(size_t(3) * NTG * NR);
+    }
+    auto scatter_targets = [&](int c) {
       TC_HIP(hipMemsetAsync(psiT.p, 0, size_t(NTG) * NR * sizeof(cx<R>), s));
       TC_HIP(hipMemsetAsync(DT.p, 0, size_t(3) * NTG * NR * sizeof(cx<R>), s));
       const unsigned gst = nblk(long(NTG) * tnpm);
+      const double* tc = ts->coef + c * tcofs;
       K(TC_K_SCATTER, 0.0, [&] {
-        hipLaunchKernelGGL((k_scatter<R>), dim3(gst), dim3(256), 0, s, ts->coef, tbox, tnpw, tkg, nbt, tnpm, NTG, -1,
+        hipLaunchKernelGGL((k_scatter<R>), dim3(gst), dim3(256), 0, s, tc, tbox, tnpw, tkg, nbt, tnpm, NTG, -1,
                            psiT.p, NR);
-        for (int c = 0; c < 3; ++c)
-          hipLaunchKernelGGL((k_scatter<R>), dim3(gst), dim3(256), 0, s, ts->coef, tbox, tnpw, tkg, nbt, tnpm, NTG, c,
-                             DT.p + size_t(c) * NTG * NR, NR);
+        for (int d = 0; d < 3; ++d)
+          hipLaunchKernelGGL((k_scatter<R>), dim3(gst), dim3(256), 0, s, tc, tbox, tnpw, tkg, nbt, tnpm, NTG, d,
+                             DT.p + size_t(d) * NTG * NR, NR);
       });
       fft3d_t<R, N>(psiT.p, NTG, +1, s, pf);
       fft3d_t<R, N>(DT.p, 3L * NTG, +1, s, pf);
-    }
-    const cx<R>* tP = ts ? psiT.p : psi.p;   // target fields
-    const cx<R>* tD = ts ? DT.p : D.p;
-    fft3d_t<R, N>(D.p, 3L * P, +1, s, pf);
-    K(TC_K_OTHER, 6.0 * fb * P, [&] {
-      hipLaunchKernelGGL((k_lattice3<R, N>), dim3(nblk(long(P) * NR)), dim3(256), 0, s, D.p, Dl.p, bm, long(P), NR,
-                         long(P) * NR);
-    });
+    };
+    if (ts && !pol) scatter_targets(0);
     ev.rec(1, s);
 
     // ---- 1: densities and Hartree-type fields (Algs. 2ah, 3a1, 3b1; 2bh1, 2bh2)
-    TC_HIP(hipMemsetAsync(loc.p, 0, 8 * NR * sizeof(cx<R>), s));
-    K(TC_K_OTHER, fb * (4.0 * P + 4.0), [&] {
-      hipLaunchKernelGGL((k_density<R, N>), dim3(nblk(NR)), dim3(256), 0, s, X, psi.p, D.p, sh.w.p, P, nJ.p,
-                         nJ.p + NR);
-    });
-    TC_HIP(hipMemcpyAsync(wk.p, nJ.p, 4 * NR * sizeof(cx<R>), hipMemcpyDeviceToDevice, s));
-    fft3d_t<R, N>(wk.p, 4, -1, s, pf);
-    K(TC_K_OTHER, fb * 9.0, [&] {
-      hipLaunchKernelGGL((k_hartree_g<R, N>), dim3(nblk(NR)), dim3(256), 0, s, rc, tHV.p, tHU.p, wk.p, wk.p + NR,
-                         wk.p + 4 * NR);
-    });
-    fft3d_t<R, N>(wk.p + 4 * NR, 5, +1, s, pf);
-    TC_HIP(hipMemcpyAsync(loc.p, wk.p + 4 * NR, 5 * NR * sizeof(cx<R>), hipMemcpyDeviceToDevice, s));
-    K(TC_K_OTHER, fb * 7.0, [&] {
-      hipLaunchKernelGGL((k_mul_vec_scalar<R, N>), dim3(nblk(NR)), dim3(256), 0, s, loc.p + NR, nJ.p, wk.p);
-    });
-    fft3d_t<R, N>(wk.p, 3, -1, s, pf);
-    K(TC_K_OTHER, fb * 4.0, [&] {
-      hipLaunchKernelGGL((k_gdiv<R, N>), dim3(nblk(NR)), dim3(256), 0, s, rc, tHU.p, wk.p, wk.p + 3 * NR);
-    });
-    fft3d_t<R, N>(wk.p + 3 * NR, 1, +1, s, pf);
-    TC_HIP(hipMemcpyAsync(loc.p + 5 * NR, wk.p + 3 * NR, NR * sizeof(cx<R>), hipMemcpyDeviceToDevice, s));
-    ev.rec(2, s);
-
-    // ---- 2: occupied-occupied pair pass (Algs. 3a2, 3a4 and 3b2/3b5 first loops)
-    const int chunk = (P + S - 1) / S;
-    if (keepA) {
-      for (int t0 = 0; t0 < P; t0 += T) {
-        const int nt = std::min(T, P - t0);
-        const long npair = long(nt) * P;
-        const FusedArgs fa{P, nt, t0, S, chunk};
-        K(TC_K_XY_PAIR_TGT, fb * (npair + nt + P), [&] {
-          hipLaunchKernelGGL((k_pair_xy<R, N, false>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, X, psi.p, fa,
-                             bufA.p);
-        });
-        K(TC_K_ZCONV_A1, fb * 6.0 * npair + tabB, [&] {
-          zconv<OP_A1>(s, bufA.p, allB.p + size_t(t0) * P * 5 * NR, npair, t0, miT, tb, 1);
-        });
-      }
-    }
-    TC_HIP(hipMemsetAsync(H3a4.p, 0, size_t(3) * P * NR * sizeof(cx<R>), s));
-    if (bitc) TC_HIP(hipMemsetAsync(H3bc.p, 0, size_t(3) * P * NR * sizeof(cx<R>), s));
-    if (need_occ) {
-      for (int a0 = 0; a0 < P; a0 += T) {
-        const int nt = std::min(T, P - a0);
-        const long npair = long(nt) * P;
-        const FusedArgs fa{P, nt, a0, S, chunk};
-        if (keepA && bitc) {
-          // row a = a0 + t, partner b = q: V21 from the stored pair b P + a (density conj(chi_a) psi_b at
-          // k_b - k_a), V12 from the stored pair a P + b (conj(chi_b) psi_a at k_a - k_b), fields 1..4
-          K(TC_K_FUSED_OB, fb * (8.0 * npair + 2.0 * P) + 7.0 * fb * nt * S, [&] {
-            hipLaunchKernelGGL((k_fused_OB<R, N>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s,
-                               allB.p + (size_t(a0) * 5 + 1) * NR, allB.p + (size_t(a0) * 5 * P + 1) * NR, psi.p, X,
-                               sh.w.p, fa, mi, rc, dfr.p, h5cpart.p, H3part.p, Hbpart.p, 5L, 5L * P, 5L * P, 5L);
-          });
-          K(TC_K_SUM_PARTS, 7.0 * fb * nt * (S + 1), [&] {
-            hipLaunchKernelGGL((k_sum_parts_ob<R, N>), dim3(nblk(long(nt) * NR)), dim3(256), 0, s, S, nt, a0,
-                               h5cpart.p, H3part.p, Hbpart.p, h5c.p, H3a4.p, H3bc.p);
-          });
-        } else if (keepA) {
-          // row a = a0 + t, partner b = q: fields 1..4 of the stored pair b P + a
-          K(TC_K_FUSED_O, fb * (4.0 * npair + P) + 3.5 * fb * nt * S, [&] {
-            hipLaunchKernelGGL((k_fused_O<R, N>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s,
-                               allB.p + (size_t(a0) * 5 + 1) * NR, psi.p, sh.w.p, fa, mi, rc, dfr.p, h5part.p,
-                               H3part.p, 5L, 5L * P);
-          });
-          K(TC_K_SUM_PARTS, 4.0 * fb * nt * (S + 1), [&] {
-            hipLaunchKernelGGL((k_sum_parts<R, N>), dim3(nblk(long(nt) * NR)), dim3(256), 0, s, 0, S, nt, a0, 0,
-                               h5part.p, H3part.p, nullptr, nullptr, h5.p, H3a4.p, nullptr, nullptr);
-          });
-        } else if (!bitc) {
-          K(TC_K_XY_PAIR_OCC, fb * (npair + nt + P), [&] {
-            hipLaunchKernelGGL((k_pair_xy<R, N, true>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, psi.p, psi.p,
-                               fa, bufA.p);
-          });
-          K(TC_K_ZCONV_OCC, fb * 5.0 * npair + tabB, [&] {
-            zconv<OP_O>(s, npair, a0, mi, tb, 0);
-          });
-          K(TC_K_FUSED_O, fb * (4.0 * npair + P) + 3.5 * fb * nt * S, [&] {
-            hipLaunchKernelGGL((k_fused_O<R, N>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, bufB.p, psi.p, sh.w.p,
-                               fa, mi, rc, dfr.p, h5part.p, H3part.p);
-          });
-          K(TC_K_SUM_PARTS, 4.0 * fb * nt * (S + 1), [&] {
-            hipLaunchKernelGGL((k_sum_parts<R, N>), dim3(nblk(long(nt) * NR)), dim3(256), 0, s, 0, S, nt, a0, 0,
-                               h5part.p, H3part.p, nullptr, nullptr, h5.p, H3a4.p, nullptr, nullptr);
-          });
-        } else {
-          // rho21 = conj(chi_a) psi_b and rho12 = conj(chi_b) psi_a, a = a0 + t, b = q; V21 at Delta = k_b - k_a,
-          // V12 at Delta = k_a - k_b (no conjugate symmetry between them)
-          cx<R>* in12 = bufA.p + npair * NR;
-          cx<R>* out12 = bufB.p + 4 * npair * NR;
-          K(TC_K_XY_PAIR_OCC, fb * 2.0 * (npair + nt + P), [&] {
-            hipLaunchKernelGGL((k_pair_xy<R, N, true>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, X, psi.p, fa,
-                               bufA.p);
-            hipLaunchKernelGGL((k_pair_xy<R, N, false>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, X, psi.p, fa,
-                               in12);
-          });
-          K(TC_K_ZCONV_OCC, 2.0 * (fb * 5.0 * npair + tabB), [&] {
-            zconv<OP_O>(s, bufA.p, bufB.p, npair, a0, mi, tb, 0);
-            zconv<OP_O>(s, in12, out12, npair, a0, mi, tb, 1);
-          });
-          K(TC_K_FUSED_OB, fb * (8.0 * npair + 2.0 * P) + 7.0 * fb * nt * S, [&] {
-            hipLaunchKernelGGL((k_fused_OB<R, N>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, bufB.p, out12, psi.p,
-                               X, sh.w.p, fa, mi, rc, dfr.p, h5cpart.p, H3part.p, Hbpart.p);
-          });
-          K(TC_K_SUM_PARTS, 7.0 * fb * nt * (S + 1), [&] {
-            hipLaunchKernelGGL((k_sum_parts_ob<R, N>), dim3(nblk(long(nt) * NR)), dim3(256), 0, s, S, nt, a0,
-                               h5cpart.p, H3part.p, Hbpart.p, h5c.p, H3a4.p, H3bc.p);
-          });
-        }
-      }
-      K(TC_K_OTHER, fb * (5.0 * P + 4.0), [&] {
-        if (bitc)
-          hipLaunchKernelGGL((k_reduce_occ<R, N, cx<R>>), dim3(nblk(NR)), dim3(256), 0, s, h5c.p, H3bc.p, psi.p,
-                             sh.w.p, P, loc.p + 6 * NR, wk.p);
-        else
-          hipLaunchKernelGGL((k_reduce_occ<R, N, R>), dim3(nblk(NR)), dim3(256), 0, s, h5.p, H3a4.p, psi.p, sh.w.p,
-                             P, loc.p + 6 * NR, wk.p);
+    if (!pol) {
+      TC_HIP(hipMemsetAsync(loc.p, 0, 8 * NR * sizeof(cx<R>), s));
+      K(TC_K_OTHER, fb * (4.0 * P + 4.0), [&] {
+        hipLaunchKernelGGL((k_density<R, N>), dim3(nblk(NR)), dim3(256), 0, s, XS[0], psi.p, D.p, sh.w.p, P, nJ.p,
+                           nJ.p + NR);
+      });
+      TC_HIP(hipMemcpyAsync(wk.p, nJ.p, 4 * NR * sizeof(cx<R>), hipMemcpyDeviceToDevice, s));
+      fft3d_t<R, N>(wk.p, 4, -1, s, pf);
+      K(TC_K_OTHER, fb * 9.0, [&] {
+        hipLaunchKernelGGL((k_hartree_g<R, N>), dim3(nblk(NR)), dim3(256), 0, s, rc, tHV.p, tHU.p, wk.p, wk.p + NR,
+                           wk.p + 4 * NR);
+      });
+      fft3d_t<R, N>(wk.p + 4 * NR, 5, +1, s, pf);
+      TC_HIP(hipMemcpyAsync(loc.p, wk.p + 4 * NR, 5 * NR * sizeof(cx<R>), hipMemcpyDeviceToDevice, s));
+      K(TC_K_OTHER, fb * 7.0, [&] {
+        hipLaunchKernelGGL((k_mul_vec_scalar<R, N>), dim3(nblk(NR)), dim3(256), 0, s, loc.p + NR, nJ.p, wk.p);
       });
       fft3d_t<R, N>(wk.p, 3, -1, s, pf);
       K(TC_K_OTHER, fb * 4.0, [&] {
         hipLaunchKernelGGL((k_gdiv<R, N>), dim3(nblk(NR)), dim3(256), 0, s, rc, tHU.p, wk.p, wk.p + 3 * NR);
       });
       fft3d_t<R, N>(wk.p + 3 * NR, 1, +1, s, pf);
-      TC_HIP(hipMemcpyAsync(loc.p + 7 * NR, wk.p + 3 * NR, NR * sizeof(cx<R>), hipMemcpyDeviceToDevice, s));
+      TC_HIP(hipMemcpyAsync(loc.p + 5 * NR, wk.p + 3 * NR, NR * sizeof(cx<R>), hipMemcpyDeviceToDevice, s));
+    } else {
+      // wk2: [0..3] n~, J~ of channel 0, [4..7] of channel 1, [8..10] / [11..13] products or M per channel
+      for (int sp = 0; sp < 2; ++sp) {
+        TC_HIP(hipMemsetAsync(LOC[sp], 0, 8 * NR * sizeof(cx<R>), s));
+        K(TC_K_OTHER, fb * (4.0 * P + 4.0), [&] {
+          hipLaunchKernelGGL((k_density<R, N>), dim3(nblk(NR)), dim3(256), 0, s, XS[sp], PSI[sp], DD[sp], W[sp], P,
+                             NJ[sp], NJ[sp] + NR);
+        });
+        TC_HIP(hipMemcpyAsync(wk2.p + 4 * sp * NR, NJ[sp], 4 * NR * sizeof(cx<R>), hipMemcpyDeviceToDevice, s));
+      }
+      fft3d_t<R, N>(wk2.p, 8, -1, s, pf);
+      for (int sp = 0; sp < 2; ++sp) {
+        const int o = 1 - sp;
+        K(TC_K_OTHER, fb * 13.0, [&] {
+          hipLaunchKernelGGL((k_hartree_g2<R, N>), dim3(nblk(NR)), dim3(256), 0, s, rc, tHVp.p, tHVa.p, tHUp.p, tHUa.p,
+                             wk2.p + 4 * sp * NR, wk2.p + (4 * sp + 1) * NR, wk2.p + 4 * o * NR,
+                             wk2.p + (4 * o + 1) * NR, wk.p);
+        });
+        fft3d_t<R, N>(wk.p, 5, +1, s, pf);
+        TC_HIP(hipMemcpyAsync(LOC[sp], wk.p, 5 * NR * sizeof(cx<R>), hipMemcpyDeviceToDevice, s));
+      }
+      // 3b1: sum_s1 -i G . u^{s s1} FT(h1^{s1} n_{s1})
+      for (int sp = 0; sp < 2; ++sp)
+        K(TC_K_OTHER, fb * 7.0, [&] {
+          hipLaunchKernelGGL((k_mul_vec_scalar<R, N>), dim3(nblk(NR)), dim3(256), 0, s, LOC[sp] + NR, NJ[sp],
+                             wk2.p + (8 + 3 * sp) * NR);
+        });
+      fft3d_t<R, N>(wk2.p + 8 * NR, 6, -1, s, pf);
+      for (int sp = 0; sp < 2; ++sp) {
+        const int o = 1 - sp;
+        K(TC_K_OTHER, fb * 7.0, [&] {
+          hipLaunchKernelGGL((k_gdiv2<R, N>), dim3(nblk(NR)), dim3(256), 0, s, rc, tHUp.p, tHUa.p,
+                             wk2.p + (8 + 3 * sp) * NR, wk2.p + (8 + 3 * o) * NR, wk.p);
+        });
+        fft3d_t<R, N>(wk.p, 1, +1, s, pf);
+        TC_HIP(hipMemcpyAsync(LOC[sp] + 5 * NR, wk.p, NR * sizeof(cx<R>), hipMemcpyDeviceToDevice, s));
+      }
     }
-    K(TC_K_OTHER, 6.0 * fb * P, [&] {
-      hipLaunchKernelGGL((k_lattice3<R, N>), dim3(nblk(long(P) * NR)), dim3(256), 0, s, H3a4.p, Hl.p, bm, long(P),
-                         3 * NR, NR);
-      if (bitc)   // in place: B conj(H3b), the pass-B partner field
-        hipLaunchKernelGGL((k_lattice3<R, N>), dim3(nblk(long(P) * NR)), dim3(256), 0, s, H3bc.p, H3bc.p, bm,
-                           long(P), 3 * NR, NR);
-    });
+    ev.rec(2, s);
+
+    // ---- 2: occupied-occupied pair pass (Algs. 3a2, 3a4 and 3b2/3b5 first loops), per channel
+    const int chunk = (P + S - 1) / S;
+    if (keepA) {
+      for (int c = 0; c < ns; ++c)
+        for (int t0 = 0; t0 < P; t0 += T) {
+          const int nt = std::min(T, P - t0);
+          const long npair = long(nt) * P;
+          const FusedArgs fa{P, nt, t0, S, chunk};
+          K(TC_K_XY_PAIR_TGT, fb * (npair + nt + P), [&] {
+            hipLaunchKernelGGL((k_pair_xy<R, N, false>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, XS[c], PSI[c],
+                               fa, bufA.p);
+          });
+          K(TC_K_ZCONV_A1, fb * 6.0 * npair + tabB, [&] {
+            zconv<OP_A1>(s, bufA.p, store(c) + size_t(t0) * P * 5 * NR, npair, t0, miT, tb, 1);
+          });
+        }
+    }
+    for (int c = 0; c < ns; ++c) {
+      TC_HIP(hipMemsetAsync(H3[c], 0, size_t(3) * P * NR * sizeof(cx<R>), s));
+      if (bitc) TC_HIP(hipMemsetAsync(HBC[c], 0, size_t(3) * P * NR * sizeof(cx<R>), s));
+      if (pol && bitc) {
+        TC_HIP(hipMemsetAsync(H5C[c], 0, size_t(P) * NR * sizeof(cx<R>), s));
+        TC_HIP(hipMemsetAsync(H5CA[c], 0, size_t(P) * NR * sizeof(cx<R>), s));
+      } else if (pol) {
+        TC_HIP(hipMemsetAsync(H5P[c], 0, size_t(P) * NR * sizeof(R), s));
+        TC_HIP(hipMemsetAsync(H5A[c], 0, size_t(P) * NR * sizeof(R), s));
+      }
+    }
+    if (need_occ) {
+      for (int c = 0; c < ns; ++c)
+        for (int a0 = 0; a0 < P; a0 += T) {
+          const int nt = std::min(T, P - a0);
+          const long npair = long(nt) * P;
+          const FusedArgs fa{P, nt, a0, S, chunk};
+          if (bitc) {
+            // row a = a0 + t, partner b = q: V21 from rho21 = conj(chi_a) psi_b at Delta = k_b - k_a, V12 from
+            // rho12 = conj(chi_b) psi_a at Delta = k_a - k_b (no conjugate symmetry between them); with the
+            // store they are its pairs b P + a and a P + b, fields 1..4
+            const cx<R>* b21 = bufB.p;
+            const cx<R>* b12 = bufB.p + 4 * npair * NR;
+            long sT21 = -1, sQ21 = 4, sT12 = -1, sQ12 = 4;
+            if (keepA) {
+              b21 = store(c) + (size_t(a0) * 5 + 1) * NR;
+              b12 = store(c) + (size_t(a0) * 5 * P + 1) * NR;
+              sT21 = 5;
+              sQ21 = 5L * P;
+              sT12 = 5L * P;
+              sQ12 = 5;
+            } else {
+              cx<R>* in12 = bufA.p + npair * NR;
+              cx<R>* out12 = bufB.p + 4 * npair * NR;
+              K(TC_K_XY_PAIR_OCC, fb * 2.0 * (npair + nt + P), [&] {
+                hipLaunchKernelGGL((k_pair_xy<R, N, true>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, XS[c],
+                                   PSI[c], fa, bufA.p);
+                hipLaunchKernelGGL((k_pair_xy<R, N, false>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, XS[c],
+                                   PSI[c], fa, in12);
+              });
+              K(TC_K_ZCONV_OCC, 2.0 * (fb * 5.0 * npair + tabB), [&] {
+                zconv<OP_O>(s, bufA.p, bufB.p, npair, a0, mi, tb, 0);
+                zconv<OP_O>(s, in12, out12, npair, a0, mi, tb, 1);
+              });
+            }
+            K(TC_K_FUSED_OB, fb * (8.0 * npair + 2.0 * P) + (pol ? 8.0 : 7.0) * fb * nt * S, [&] {
+              if (pol)
+                hipLaunchKernelGGL((k_fused_OB<R, N, true>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, b21, b12,
+                                   PSI[c], XS[c], W[c], fa, mi, rc, dfr.p, h5cpart.p, H3part.p, Hbpart.p, sT21, sQ21,
+                                   sT12, sQ12);
+              else
+                hipLaunchKernelGGL((k_fused_OB<R, N>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, b21, b12, PSI[c],
+                                   XS[c], W[c], fa, mi, rc, dfr.p, h5cpart.p, H3part.p, Hbpart.p, sT21, sQ21, sT12,
+                                   sQ12);
+            });
+            K(TC_K_SUM_PARTS, (pol ? 8.0 : 7.0) * fb * nt * (S + 1), [&] {
+              hipLaunchKernelGGL((k_sum_parts_ob<R, N>), dim3(nblk(long(nt) * NR)), dim3(256), 0, s, S, nt, a0,
+                                 h5cpart.p, H3part.p, Hbpart.p, H5C[c], H3[c], HBC[c]);
+              if (pol)   // the antiparallel-channel part (second half of the partials)
+                hipLaunchKernelGGL((k_sum_cx_parts<R, N>), dim3(nblk(long(nt) * NR)), dim3(256), 0, s, S, nt, a0,
+                                   h5cpart.p + size_t(S) * nt * NR, H5CA[c]);
+            });
+          } else {
+            // row a = a0 + t, partner b = q; with the store: fields 1..4 of its pair b P + a
+            const cx<R>* b4 = bufB.p;
+            long sT = -1, sQ = 4;
+            if (keepA) {
+              b4 = store(c) + (size_t(a0) * 5 + 1) * NR;
+              sT = 5;
+              sQ = 5L * P;
+            } else {
+              K(TC_K_XY_PAIR_OCC, fb * (npair + nt + P), [&] {
+                hipLaunchKernelGGL((k_pair_xy<R, N, true>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, PSI[c],
+                                   PSI[c], fa, bufA.p);
+              });
+              K(TC_K_ZCONV_OCC, fb * 5.0 * npair + tabB, [&] {
+                zconv<OP_O>(s, npair, a0, mi, tb, 0);
+              });
+            }
+            K(TC_K_FUSED_O, fb * (4.0 * npair + P) + (pol ? 4.5 : 3.5) * fb * nt * S, [&] {
+              if (pol)
+                hipLaunchKernelGGL((k_fused_O<R, N, true>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, b4, PSI[c],
+                                   W[c], fa, mi, rc, dfr.p, h5part.p, H3part.p, sT, sQ);
+              else
+                hipLaunchKernelGGL((k_fused_O<R, N>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, b4, PSI[c], W[c],
+                                   fa, mi, rc, dfr.p, h5part.p, H3part.p, sT, sQ);
+            });
+            K(TC_K_SUM_PARTS, (pol ? 5.0 : 4.0) * fb * nt * (S + 1), [&] {
+              hipLaunchKernelGGL((k_sum_parts<R, N>), dim3(nblk(long(nt) * NR)), dim3(256), 0, s, 0, S, nt, a0, 0,
+                                 h5part.p, H3part.p, nullptr, nullptr, H5P[c], H3[c], nullptr, nullptr);
+              if (pol)   // the antiparallel-channel part (second half of the partials)
+                hipLaunchKernelGGL((k_sum_real_parts<R, N>), dim3(nblk(long(nt) * NR)), dim3(256), 0, s, S, nt, a0,
+                                   h5part.p + size_t(S) * nt * NR, H5A[c]);
+            });
+          }
+        }
+      // h6 = sum w h5, M = sum w conj(H3c) psi (the 3b2 sources) and the 3b2 field
+      if (!pol) {
+        K(TC_K_OTHER, fb * (5.0 * P + 4.0), [&] {
+          if (bitc)
+            hipLaunchKernelGGL((k_reduce_occ<R, N, cx<R>>), dim3(nblk(NR)), dim3(256), 0, s, h5c.p, H3bc.p, psi.p,
+                               sh.w.p, P, loc.p + 6 * NR, wk.p);
+          else
+            hipLaunchKernelGGL((k_reduce_occ<R, N, R>), dim3(nblk(NR)), dim3(256), 0, s, h5.p, H3a4.p, psi.p, sh.w.p,
+                               P, loc.p + 6 * NR, wk.p);
+        });
+        fft3d_t<R, N>(wk.p, 3, -1, s, pf);
+        K(TC_K_OTHER, fb * 4.0, [&] {
+          hipLaunchKernelGGL((k_gdiv<R, N>), dim3(nblk(NR)), dim3(256), 0, s, rc, tHU.p, wk.p, wk.p + 3 * NR);
+        });
+        fft3d_t<R, N>(wk.p + 3 * NR, 1, +1, s, pf);
+        TC_HIP(hipMemcpyAsync(loc.p + 7 * NR, wk.p + 3 * NR, NR * sizeof(cx<R>), hipMemcpyDeviceToDevice, s));
+      } else {
+        // per channel M_s2; h6 and the 3b2 field of each target spin from both channels
+        for (int s2 = 0; s2 < 2; ++s2)
+          K(TC_K_OTHER, fb * (5.0 * P + 4.0), [&] {
+            if (bitc)
+              hipLaunchKernelGGL((k_reduce_occ<R, N, cx<R>>), dim3(nblk(NR)), dim3(256), 0, s, H5C[s2], HBC[s2],
+                                 PSI[s2], W[s2], P, LOC[s2] + 6 * NR, wk2.p + (8 + 3 * s2) * NR);
+            else
+              hipLaunchKernelGGL((k_reduce_occ<R, N, R>), dim3(nblk(NR)), dim3(256), 0, s, H5P[s2], H3[s2], PSI[s2],
+                                 W[s2], P, LOC[s2] + 6 * NR, wk2.p + (8 + 3 * s2) * NR);
+          });
+        fft3d_t<R, N>(wk2.p + 8 * NR, 6, -1, s, pf);
+        for (int sp = 0; sp < 2; ++sp) {
+          const int o = 1 - sp;
+          K(TC_K_OTHER, fb * (2.0 * P + 1.0), [&] {
+            if (bitc)
+              hipLaunchKernelGGL((k_h6_pol_c<R, N>), dim3(nblk(NR)), dim3(256), 0, s, H5C[sp], W[sp], H5CA[o], W[o], P,
+                                 LOC[sp] + 6 * NR);
+            else
+              hipLaunchKernelGGL((k_h6_pol<R, N>), dim3(nblk(NR)), dim3(256), 0, s, H5P[sp], W[sp], H5A[o], W[o], P,
+                                 LOC[sp] + 6 * NR);
+            hipLaunchKernelGGL((k_gdiv2<R, N>), dim3(nblk(NR)), dim3(256), 0, s, rc, tHUp.p, tHUa.p,
+                               wk2.p + (8 + 3 * sp) * NR, wk2.p + (8 + 3 * o) * NR, wk.p);
+          });
+          fft3d_t<R, N>(wk.p, 1, +1, s, pf);
+          TC_HIP(hipMemcpyAsync(LOC[sp] + 7 * NR, wk.p, NR * sizeof(cx<R>), hipMemcpyDeviceToDevice, s));
+        }
+      }
+    }
+    for (int c = 0; c < ns; ++c)
+      K(TC_K_OTHER, 6.0 * fb * P, [&] {
+        hipLaunchKernelGGL((k_lattice3<R, N>), dim3(nblk(long(P) * NR)), dim3(256), 0, s, H3[c], HL[c], bm, long(P),
+                           3 * NR, NR);
+        if (bitc)   // in place: B conj(H3b), the pass-B partner field
+          hipLaunchKernelGGL((k_lattice3<R, N>), dim3(nblk(long(P) * NR)), dim3(256), 0, s, HBC[c], HBC[c], bm,
+                             long(P), 3 * NR, NR);
+      });
     ev.rec(3, s);
 
     // band divergence corrections: h3 of the band orbitals as rows of the occupied-occupied pass
@@ -1553,7 +1681,7 @@ struct EngineT : Engine {
         const int nt = std::min(T, NTG - a0);
         const long npair = long(nt) * P;
         const FusedArgs fa{P, nt, a0, S, chunk};
-        hipLaunchKernelGGL((k_pair_xy<R, N, true>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, tP, psi.p, fa,
+        hipLaunchKernelGGL((k_pair_xy<R, N, true>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, psiT.p, psi.p, fa,
                            bufA.p);
         zconv<OP_O>(s, npair, a0, miT, tb, 0);
         hipLaunchKernelGGL((k_fused_O<R, N>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, bufB.p, psi.p, sh.w.p, fa,
@@ -1563,127 +1691,149 @@ struct EngineT : Engine {
       }
     }
 
-    // ---- 3/4: target batches (pass A, pass B, local terms, r -> G)
-    for (int t0 = 0; t0 < NTG; t0 += T) {
-      const int nt = std::min(T, NTG - t0);
-      const long npair = long(nt) * P;
-      TC_HIP(hipMemsetAsync(acc.p, 0, size_t(kAccSlots) * T * NR * sizeof(cx<double>), s));
-      TC_HIP(hipMemsetAsync(h4.p, 0, size_t(3) * T * NR * sizeof(cx<R>), s));
-      if (!t_arena)
-        for (int i = 0; i < 3; ++i) {
-          hipEvent_t e;
-          TC_HIP(hipEventCreate(&e));
-          bev.push_back(e);
-        }
-      hipEvent_t* be = t_arena ? nullptr : &bev[bev.size() - 3];
-      if (be) TC_HIP(hipEventRecord(be[0], s));
-      const double part = fb * nt * S;   // one working-precision field per (chunk, target)
-      if (need_A) {
-        const FusedArgs fa{P, nt, t0, S, chunk};
-        const cx<R>* zA = keepA ? allB.p + size_t(t0) * P * 5 * NR : bufB.p;
-        if (!keepA) {
-          K(TC_K_XY_PAIR_TGT, fb * (npair + nt + P), [&] {
-            hipLaunchKernelGGL((k_pair_xy<R, N, false>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, X, tP, fa,
-                               bufA.p);
+    // ---- 3/4: target batches of each channel (pass A, pass B, local terms, r -> G); partners of the
+    // target's own spin
+    for (int c = 0; c < ns; ++c) {
+      const int o = pol ? 1 - c : 0;
+      if (ts && pol) scatter_targets(c);
+      const cx<R>* tP = ts ? psiT.p : PSI[c];   // target fields
+      const cx<R>* tD = ts ? DT.p : DD[c];
+      for (int t0 = 0; t0 < NTG; t0 += T) {
+        const int nt = std::min(T, NTG - t0);
+        const long npair = long(nt) * P;
+        TC_HIP(hipMemsetAsync(acc.p, 0, size_t(kAccSlots) * T * NR * sizeof(cx<double>), s));
+        TC_HIP(hipMemsetAsync(h4.p, 0, size_t(3) * T * NR * sizeof(cx<R>), s));
+        if (!t_arena)
+          for (int i = 0; i < 3; ++i) {
+            hipEvent_t e;
+            TC_HIP(hipEventCreate(&e));
+            bev.push_back(e);
+          }
+        hipEvent_t* be = t_arena ? nullptr : &bev[bev.size() - 3];
+        if (be) TC_HIP(hipEventRecord(be[0], s));
+        const double part = fb * nt * S;   // one working-precision field per (chunk, target)
+        if (need_A) {
+          const FusedArgs fa{P, nt, t0, S, chunk};
+          const cx<R>* zA = keepA ? store(c) + size_t(t0) * P * 5 * NR : bufB.p;
+          if (!keepA) {
+            K(TC_K_XY_PAIR_TGT, fb * (npair + nt + P), [&] {
+              hipLaunchKernelGGL((k_pair_xy<R, N, false>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, XS[c], tP, fa,
+                                 bufA.p);
+            });
+            K(TC_K_ZCONV_A1, fb * 6.0 * npair + tabB, [&] {
+              zconv<OP_A1>(s, npair, t0, miT, tb, 1);
+            });
+          }
+          // POL: the antiparallel 3b6 sources take the other channel's density; CN: complex densities
+          const cx<R>* nA = pol ? NJ[o] : nullptr;
+          const int do3b6 = int(m.m3b6 != 0);
+          K(TC_K_FUSED_A, fb * ((m.m3b6 ? 9.0 : 5.0) * npair + 8.0 * P + nt) + 6.0 * part, [&] {
+            const dim3 g(unsigned(nt) * N * S), b(NTH);
+            if (pol && bitc)
+              hipLaunchKernelGGL((k_fused_A<R, N, true, true>), g, b, 0, s, zA, PSI[c], DL[c], HL[c], NJ[c], W[c], fa,
+                                 m, do3b6, miT, bm, mm, dfr.p, bufA.p, gpart.p, h4part.p, nA);
+            else if (pol)
+              hipLaunchKernelGGL((k_fused_A<R, N, true, false>), g, b, 0, s, zA, PSI[c], DL[c], HL[c], NJ[c], W[c], fa,
+                                 m, do3b6, miT, bm, mm, dfr.p, bufA.p, gpart.p, h4part.p, nA);
+            else if (bitc)
+              hipLaunchKernelGGL((k_fused_A<R, N, false, true>), g, b, 0, s, zA, PSI[c], DL[c], HL[c], NJ[c], W[c], fa,
+                                 m, do3b6, miT, bm, mm, dfr.p, bufA.p, gpart.p, h4part.p, nA);
+            else
+              hipLaunchKernelGGL((k_fused_A<R, N, false, false>), g, b, 0, s, zA, PSI[c], DL[c], HL[c], NJ[c], W[c],
+                                 fa, m, do3b6, miT, bm, mm, dfr.p, bufA.p, gpart.p, h4part.p, nA);
           });
-          K(TC_K_ZCONV_A1, fb * 6.0 * npair + tabB, [&] {
-            zconv<OP_A1>(s, npair, t0, miT, tb, 1);
+          K(TC_K_SUM_PARTS, 6.0 * part + 6.0 * fd * nt + 3.0 * fb * nt, [&] {
+            hipLaunchKernelGGL((k_sum_parts<R, N>), dim3(nblk(long(nt) * NR)), dim3(256), 0, s, 1, S, nt, t0, 0,
+                               nullptr, nullptr, gpart.p, h4part.p, nullptr, nullptr, acc.p, h4.p);
           });
+          if (ts && ts->bdh4) {   // band k-points: h4 of Alg. 3a3 (h3 of Alg. 3b4) corrected at q1 -> k, then <psi_mu|h4_j>
+            hipLaunchKernelGGL((k_band_dh4<R, N>), dim3(nblk(long(nt) * NR)), dim3(256), 0, s, tP, ts->bdh4, ts->bV,
+                               t0, nt, nbt, h4.p);
+            hipLaunchKernelGGL((k_band_dot<R, R, R>), dim3(nt * nbt * 3), dim3(256), 0, s, tP, NR, 0L, h4.p, 3 * NR,
+                               NR, t0, (const cx<R>*)nullptr, 0L, t0, nbt, 3, NR, ts->OBh4);
+          }
+          if (m.m3b6 && !need_B) {
+            K(TC_K_ZCONV_A2, fb * 5.0 * npair + tabB, [&] {
+              zconv<OP_A2>(s, npair, t0, miT, tb, 1);
+            });
+            K(TC_K_FUSED_Y, fb * (npair + P) + part, [&] {
+              hipLaunchKernelGGL((k_fused_Y<R, N>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, bufB.p, PSI[c],
+                                 W[c], fa, 1.0, gpart.p);
+            });
+            K(TC_K_SUM_PARTS, part + 2.0 * fd * nt, [&] {
+              hipLaunchKernelGGL((k_sum_parts<R, N>), dim3(nblk(long(nt) * NR)), dim3(256), 0, s, 2, S, nt, t0, 2,
+                                 nullptr, nullptr, gpart.p, nullptr, nullptr, nullptr, acc.p, nullptr);
+            });
+          }
         }
-        K(TC_K_FUSED_A, fb * ((m.m3b6 ? 9.0 : 5.0) * npair + 8.0 * P + nt) + 6.0 * part, [&] {
-          if (bitc)   // complex density
-            hipLaunchKernelGGL((k_fused_A<R, N, false, true>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, zA,
-                               psi.p, Dl.p, Hl.p, nJ.p, sh.w.p, fa, m, int(m.m3b6 != 0), miT, bm, mm, dfr.p, bufA.p,
-                               gpart.p, h4part.p);
-          else
-            hipLaunchKernelGGL((k_fused_A<R, N, false, false>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, zA,
-                               psi.p, Dl.p, Hl.p, nJ.p, sh.w.p, fa, m, int(m.m3b6 != 0), miT, bm, mm, dfr.p, bufA.p,
-                               gpart.p, h4part.p);
-        });
-        K(TC_K_SUM_PARTS, 6.0 * part + 6.0 * fd * nt + 3.0 * fb * nt, [&] {
-          hipLaunchKernelGGL((k_sum_parts<R, N>), dim3(nblk(long(nt) * NR)), dim3(256), 0, s, 1, S, nt, t0, 0, nullptr,
-                             nullptr, gpart.p, h4part.p, nullptr, nullptr, acc.p, h4.p);
-        });
-        if (ts && ts->bdh4) {   // band k-points: h4 of Alg. 3a3 (h3 of Alg. 3b4) corrected at q1 -> k, then <psi_mu|h4_j>
-          hipLaunchKernelGGL((k_band_dh4<R, N>), dim3(nblk(long(nt) * NR)), dim3(256), 0, s, tP, ts->bdh4, ts->bV, t0,
-                             nt, nbt, h4.p);
-          hipLaunchKernelGGL((k_band_dot<R, R, R>), dim3(nt * nbt * 3), dim3(256), 0, s, tP, NR, 0L, h4.p, 3 * NR, NR,
-                             t0, (const cx<R>*)nullptr, 0L, t0, nbt, 3, NR, ts->OBh4);
-        }
-        if (m.m3b6 && !need_B) {
-          K(TC_K_ZCONV_A2, fb * 5.0 * npair + tabB, [&] {
-            zconv<OP_A2>(s, npair, t0, miT, tb, 1);
+        if (be) TC_HIP(hipEventRecord(be[1], s));
+        if (need_B) {
+          // With 3b6 selected, its z stage (Alg. 3b6, sources in bufA) and pass B's (Algs. 3b3-3b5, sources in
+          // bufB) both multiply by the parallel-channel u~ and end in the same partner sum: one OP_A2 z stage
+          // also takes the pass-B sources (with -u~_par: OP_A2 carries -i where pass B carries +i), and one
+          // partner sum serves both (three-body energy slot of pass B).
+          const bool merged = need_A && m.m3b6;
+          const FusedArgs fy{P, nt, t0, S, chunk};
+          cx<R>* srcB = merged ? bufB.p : bufA.p;
+          cx<R>* zout = merged ? bufB.p + size_t(2) * npair * NR : bufB.p;
+          K(TC_K_OTHER, fb * 13.0 * nt, [&] {
+            hipLaunchKernelGGL((k_passB_Z<R, N>), dim3(nblk(long(nt) * NR)), dim3(256), 0, s, tP, tD, LOC[c] + NR,
+                               h4.p, t0, nt, NTG, m, bm, Z.p);
           });
+          K(TC_K_XY_PASSB, fb * (2.0 * npair + 4.0 * P + 4.0 * nt), [&] {
+            hipLaunchKernelGGL((k_passB_xy<R, N>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, tP, XS[c], Z.p,
+                               bitc ? HBC[c] : HL[c], fy, miT, dfr.p, R(m.m3b5), srcB);
+          });
+          if (merged) {
+            K(TC_K_ZCONV_A2, fb * 7.0 * npair + tabB, [&] {
+              zconv<OP_A2>(s, bufA.p, zout, npair, t0, miT, tb, 1, bufB.p);
+            });
+          } else {
+            K(TC_K_ZCONV_B, fb * 3.0 * npair + tabB, [&] {
+              zconv<OP_B>(s, npair, t0, miT, tb, 1);
+            });
+          }
           K(TC_K_FUSED_Y, fb * (npair + P) + part, [&] {
-            hipLaunchKernelGGL((k_fused_Y<R, N>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, bufB.p, psi.p,
-                               sh.w.p, fa, 1.0, gpart.p);
+            hipLaunchKernelGGL((k_fused_Y<R, N>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, zout, PSI[c], W[c], fy,
+                               1.0, gpart.p);
           });
           K(TC_K_SUM_PARTS, part + 2.0 * fd * nt, [&] {
-            hipLaunchKernelGGL((k_sum_parts<R, N>), dim3(nblk(long(nt) * NR)), dim3(256), 0, s, 2, S, nt, t0, 2,
+            hipLaunchKernelGGL((k_sum_parts<R, N>), dim3(nblk(long(nt) * NR)), dim3(256), 0, s, 2, S, nt, t0, 3,
                                nullptr, nullptr, gpart.p, nullptr, nullptr, nullptr, acc.p, nullptr);
           });
         }
-      }
-      if (be) TC_HIP(hipEventRecord(be[1], s));
-      if (need_B) {
-        // With 3b6 selected, its z stage (Alg. 3b6, sources in bufA) and pass B's (Algs. 3b3-3b5, sources in
-        // bufB) both multiply by the parallel-channel u~ and end in the same partner sum: one OP_A2 z stage
-        // also takes the pass-B sources (with -u~_par: OP_A2 carries -i where pass B carries +i), and one
-        // partner sum serves both (three-body energy slot of pass B).
-        const bool merged = need_A && m.m3b6;
-        const FusedArgs fy{P, nt, t0, S, chunk};
-        cx<R>* srcB = merged ? bufB.p : bufA.p;
-        cx<R>* zout = merged ? bufB.p + size_t(2) * npair * NR : bufB.p;
-        K(TC_K_OTHER, fb * 13.0 * nt, [&] {
-          hipLaunchKernelGGL((k_passB_Z<R, N>), dim3(nblk(long(nt) * NR)), dim3(256), 0, s, tP, tD, loc.p + NR,
-                             h4.p, t0, nt, NTG, m, bm, Z.p);
+        if (be) TC_HIP(hipEventRecord(be[2], s));
+        K(TC_K_OTHER, fb * 16.0 * nt + 8.0 * fd * nt, [&] {
+          hipLaunchKernelGGL((k_local<R, N>), dim3(nblk(long(nt) * NR)), dim3(256), 0, s, tP, tD, LOC[c], h4.p, t0, nt,
+                             NTG, m, acc.p, g.p);
+          if (!ts)
+            hipLaunchKernelGGL((k_epart<R, N>), dim3(kAccSlots * nt), dim3(256), 0, s, XS[c], acc.p, t0, nt,
+                               sh.epart.p + size_t(kAccSlots) * c * P);
         });
-        K(TC_K_XY_PASSB, fb * (2.0 * npair + 4.0 * P + 4.0 * nt), [&] {
-          hipLaunchKernelGGL((k_passB_xy<R, N>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, tP, X, Z.p,
-                             bitc ? H3bc.p : Hl.p, fy, miT, dfr.p, R(m.m3b5), srcB);
-        });
-        if (merged) {
-          K(TC_K_ZCONV_A2, fb * 7.0 * npair + tabB, [&] {
-            zconv<OP_A2>(s, bufA.p, zout, npair, t0, miT, tb, 1, bufB.p);
-          });
-        } else {
-          K(TC_K_ZCONV_B, fb * 3.0 * npair + tabB, [&] {
-            zconv<OP_B>(s, npair, t0, miT, tb, 1);
-          });
-        }
-        K(TC_K_FUSED_Y, fb * (npair + P) + part, [&] {
-          hipLaunchKernelGGL((k_fused_Y<R, N>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, zout, psi.p, sh.w.p,
-                             fy, 1.0, gpart.p);
-        });
-        K(TC_K_SUM_PARTS, part + 2.0 * fd * nt, [&] {
-          hipLaunchKernelGGL((k_sum_parts<R, N>), dim3(nblk(long(nt) * NR)), dim3(256), 0, s, 2, S, nt, t0, 3, nullptr,
-                             nullptr, gpart.p, nullptr, nullptr, nullptr, acc.p, nullptr);
+        fft3d_t<R, N>(g.p, nt, -1, s, pf);
+        K(TC_K_OTHER, 0.0, [&] {
+          hipLaunchKernelGGL((k_gather<R>), dim3(nblk(long(nt) * tnpm)), dim3(256), 0, s, g.p, tbox, tnpw, nbt, tnpm,
+                             t0, nt, 1.0 / double(NR), (ts ? ts->out + c * tcofs : sh.out.p + c * cofs), NR);
         });
       }
-      if (be) TC_HIP(hipEventRecord(be[2], s));
-      K(TC_K_OTHER, fb * 16.0 * nt + 8.0 * fd * nt, [&] {
-        hipLaunchKernelGGL((k_local<R, N>), dim3(nblk(long(nt) * NR)), dim3(256), 0, s, tP, tD, loc.p, h4.p, t0,
-                           nt, NTG, m, acc.p, g.p);
-        if (!ts)
-          hipLaunchKernelGGL((k_epart<R, N>), dim3(kAccSlots * nt), dim3(256), 0, s, X, acc.p, t0, nt, sh.epart.p);
-      });
-      fft3d_t<R, N>(g.p, nt, -1, s, pf);
-      K(TC_K_OTHER, 0.0, [&] {
-        hipLaunchKernelGGL((k_gather<R>), dim3(nblk(long(nt) * tnpm)), dim3(256), 0, s, g.p, tbox, tnpw, nbt, tnpm,
-                           t0, nt, 1.0 / double(NR), ts ? ts->out : sh.out.p, NR);
-      });
     }
-    if (ts && ts->OBh4) band_grid(s, sh, pb, *ts, NTG, tP, tbox, tnpw, tkg, tnpm, rc);
+    if (ts && ts->OBh4) band_grid(s, sh, pb, *ts, NTG, psiT.p, tbox, tnpw, tkg, tnpm, rc);
     ev.rec(4, s);
 
     // ---- 5: kinetic energy and FP64 corrections
     K(TC_K_CORR, 0.0, [&] {
       if (!ts) {
-        hipLaunchKernelGGL(k_kinetic, dim3(P), dim3(256), 0, s, bitc ? sh.coefL.p : sh.coef.p, sh.coef.p, sh.kg.p,
-                           sh.npw.p, nb, pb.npw_max, sh.tkin.p);
-        TC_HIP(hipMemsetAsync(sh.ecorr.p, 0, size_t(2) * P * sizeof(double), s));
+        for (int c = 0; c < ns; ++c)
+          hipLaunchKernelGGL(k_kinetic, dim3(P), dim3(256), 0, s, (bitc ? sh.coefL.p : sh.coef.p) + c * cofs,
+                             sh.coef.p + c * cofs, sh.kg.p, sh.npw.p, nb, pb.npw_max, sh.tkin.p + size_t(c) * P);
+        TC_HIP(hipMemsetAsync(sh.ecorr.p, 0, size_t(2) * ns * P * sizeof(double), s));
       }
-      if (need_corr(pb, m) && !(ts && ts->band)) corrections(s, sh, pb, m, ts);
+      if (need_corr(pb, m) && !(ts && ts->band)) {
+        if (pol)
+          corrections_pol(s, sh, pb, m, ts);
+        else
+          corrections(s, sh, pb, m, ts);
+      }
     });
     ev.rec(5, s);
     ev.sync(5, s);
@@ -2016,385 +2166,6 @@ struct EngineT : Engine {
                          sh.tkin.p);
       TC_HIP(hipMemsetAsync(sh.ecorr.p, 0, size_t(2) * P * sizeof(double), s));
       if (need_corr(pb, m)) corrections(s, sh, pb, m, nullptr);
-    });
-    ev.rec(5, s);
-    ev.sync(5, s);
-    if (pf && pf->on) pf->collect();
-    stage_ms[0] = ev.ms(0, 1);
-    stage_ms[1] = ev.ms(1, 2);
-    stage_ms[2] = ev.ms(2, 3);
-    stage_ms[3] = msA;
-    stage_ms[4] = msB;
-    stage_ms[5] = ev.ms(3, 5) - msA - msB;
-  }
-
-  // Spin-polarised application (TC mode): each spin channel has its own orbitals.  Exchange-type terms
-  // pair orbitals of one spin; the Hartree-type fields, 3a2 (h6), 3b1, 3b2 and the 3b6 chain take the
-  // parallel-channel kernels for the own spin and the antiparallel-channel ones for the other spin.
-  // Layout: channel sp's coefficients, outputs and energies follow those of channel 0 (spin-major).
-  // ts: trial vectors of both channels ([2][nk][nvec][npw_max], channel-major, as the output); each channel's
-  // vectors take the target role against its own channel's partners
-  void apply_pol(hipStream_t s, Shared& sh, const Problem& pb, double* stage_ms, const TargetSet* ts = nullptr) {
-    const int P = pb.P();
-    const int nb = pb.nb;
-    const int npm = pb.npw_max;
-    const int nbt = ts ? ts->nvec : nb;
-    const int NTG = pb.nk * nbt;
-    const size_t tcofs = size_t(2) * NTG * npm;   // doubles per channel of the trial vectors
-    Masks m = make_masks(pb.mask);
-    if (pb.negate_b) {   // v2 -> v2^dagger (the left gradient of the biorthogonal mode)
-      m.m2bh1 = -m.m2bh1;
-      m.m2bh2 = -m.m2bh2;
-      m.m2bx1 = -m.m2bx1;
-      m.m2bx2 = -m.m2bx2;
-    }
-    ensure(pb, pair_budget(pb));
-    const MeshInfo mi{pb.n1, pb.n2, pb.n3, nb, P, nb};
-    const MeshInfo miT{pb.n1, pb.n2, pb.n3, nb, P, nbt};   // target passes
-    Recip rc;
-    for (int i = 0; i < 9; ++i) rc.b[i] = pb.B[i];
-    Basis<R> bm, mm;
-    for (int i = 0; i < 9; ++i) bm.b[i] = R(pb.B[i]);
-    for (int d = 0; d < 3; ++d)
-      for (int e = 0; e < 3; ++e)
-        mm.b[3 * d + e] = R(pb.B[3 * d] * pb.B[3 * e] + pb.B[3 * d + 1] * pb.B[3 * e + 1] + pb.B[3 * d + 2] * pb.B[3 * e + 2]);
-    const Tables tb{tV.p, tU1.p, tU2.p, dfr.p};
-    const double fb = double(sizeof(cx<R>)) * NR;
-    const double fd = double(sizeof(cx<double>)) * NR;
-    const double tabB = 3.0 * double(sizeof(R)) * NR * double((2 * pb.n1 - 1) * (2 * pb.n2 - 1) * (2 * pb.n3 - 1));
-    Prof* pf = prof;
-    auto K = [&](int id, double bytes, auto&& launch) {
-      ProfScope ps(pf, s, id, bytes);
-      launch();
-    };
-    if (ts) {
-      psiT.alloc(size_t(NTG) * NR);
-      DT.alloc(size_t(3) * NTG * NR);
-    }
-    cx<R>* PSI[2] = {psi.p, psi1.p};
-    cx<R>* DD[2] = {D.p, D1.p};
-    cx<R>* DL[2] = {Dl.p, Dl1.p};
-    cx<R>* HL[2] = {Hl.p, Hl1.p};
-    cx<R>* H3[2] = {H3a4.p, H3a4_1.p};
-    cx<R>* NJ[2] = {nJ.p, nJ1.p};
-    cx<R>* LOC[2] = {loc.p, loc1.p};
-    R* H5P[2] = {h5.p, h5_1.p};
-    R* H5A[2] = {h5a0.p, h5a1.p};
-    const double* W[2] = {sh.w.p, sh.w.p + P};
-    const size_t cofs = size_t(2) * P * npm;   // doubles per channel in coefficient arrays
-    // biorthogonal mode: the bras of each channel are its left orbitals chi (TC mode: psi)
-    const bool bitc = pb.bitc;
-    cx<R>* CHI[2] = {chi.p, chi1.p};
-    const cx<R>* XS[2] = {bitc ? chi.p : psi.p, bitc ? chi1.p : psi1.p};
-    cx<R>* H5C[2] = {h5c.p, h5c_1.p};     // complex h5, parallel- and antiparallel-channel parts
-    cx<R>* H5CA[2] = {h5ca0.p, h5ca1.p};
-    cx<R>* HBC[2] = {H3bc.p, H3bc_1.p};   // conj(H3b), then its lattice components
-    Events ev(6);
-    double msA = 0, msB = 0;
-    ev.rec(0, s);
-
-    // ---- 0: G -> r for both channels
-    const unsigned gsc = nblk(long(P) * npm);
-    for (int sp = 0; sp < 2; ++sp) {
-      TC_HIP(hipMemsetAsync(PSI[sp], 0, size_t(P) * NR * sizeof(cx<R>), s));
-      TC_HIP(hipMemsetAsync(DD[sp], 0, size_t(3) * P * NR * sizeof(cx<R>), s));
-      const double* cf = sh.coef.p + sp * cofs;
-      K(TC_K_SCATTER, 0.0, [&] {
-        hipLaunchKernelGGL((k_scatter<R>), dim3(gsc), dim3(256), 0, s, cf, sh.boxidx.p, sh.npw.p, sh.kg.p, nb, npm, P,
-                           -1, PSI[sp], NR);
-        for (int c = 0; c < 3; ++c)
-          hipLaunchKernelGGL((k_scatter<R>), dim3(gsc), dim3(256), 0, s, cf, sh.boxidx.p, sh.npw.p, sh.kg.p, nb, npm,
-                             P, c, DD[sp] + size_t(c) * P * NR, NR);
-      });
-      fft3d_t<R, N>(PSI[sp], P, +1, s, pf);
-      fft3d_t<R, N>(DD[sp], 3L * P, +1, s, pf);
-      if (bitc) {
-        TC_HIP(hipMemsetAsync(CHI[sp], 0, size_t(P) * NR * sizeof(cx<R>), s));
-        K(TC_K_SCATTER, 0.0, [&] {
-          hipLaunchKernelGGL((k_scatter<R>), dim3(gsc), dim3(256), 0, s, sh.coefL.p + sp * cofs, sh.boxidx.p,
-                             sh.npw.p, sh.kg.p, nb, npm, P, -1, CHI[sp], NR);
-        });
-        fft3d_t<R, N>(CHI[sp], P, +1, s, pf);
-      }
-      K(TC_K_OTHER, 6.0 * fb * P, [&] {
-        hipLaunchKernelGGL((k_lattice3<R, N>), dim3(nblk(long(P) * NR)), dim3(256), 0, s, DD[sp], DL[sp], bm, long(P),
-                           NR, long(P) * NR);
-      });
-    }
-    ev.rec(1, s);
-
-    // ---- 1: densities of both channels; Hartree-type fields of each target spin
-    // wk2: [0..3] n~, J~ of channel 0, [4..7] of channel 1, [8..10] / [11..13] products or M per channel
-    for (int sp = 0; sp < 2; ++sp) {
-      TC_HIP(hipMemsetAsync(LOC[sp], 0, 8 * NR * sizeof(cx<R>), s));
-      K(TC_K_OTHER, fb * (4.0 * P + 4.0), [&] {
-        hipLaunchKernelGGL((k_density<R, N>), dim3(nblk(NR)), dim3(256), 0, s, XS[sp], PSI[sp], DD[sp], W[sp], P,
-                           NJ[sp], NJ[sp] + NR);
-      });
-      TC_HIP(hipMemcpyAsync(wk2.p + 4 * sp * NR, NJ[sp], 4 * NR * sizeof(cx<R>), hipMemcpyDeviceToDevice, s));
-    }
-    fft3d_t<R, N>(wk2.p, 8, -1, s, pf);
-    for (int sp = 0; sp < 2; ++sp) {
-      const int o = 1 - sp;
-      K(TC_K_OTHER, fb * 13.0, [&] {
-        hipLaunchKernelGGL((k_hartree_g2<R, N>), dim3(nblk(NR)), dim3(256), 0, s, rc, tHVp.p, tHVa.p, tHUp.p, tHUa.p,
-                           wk2.p + 4 * sp * NR, wk2.p + (4 * sp + 1) * NR, wk2.p + 4 * o * NR,
-                           wk2.p + (4 * o + 1) * NR, wk.p);
-      });
-      fft3d_t<R, N>(wk.p, 5, +1, s, pf);
-      TC_HIP(hipMemcpyAsync(LOC[sp], wk.p, 5 * NR * sizeof(cx<R>), hipMemcpyDeviceToDevice, s));
-    }
-    // 3b1: sum_s1 -i G . u^{s s1} FT(h1^{s1} n_{s1})
-    for (int sp = 0; sp < 2; ++sp)
-      K(TC_K_OTHER, fb * 7.0, [&] {
-        hipLaunchKernelGGL((k_mul_vec_scalar<R, N>), dim3(nblk(NR)), dim3(256), 0, s, LOC[sp] + NR, NJ[sp],
-                           wk2.p + (8 + 3 * sp) * NR);
-      });
-    fft3d_t<R, N>(wk2.p + 8 * NR, 6, -1, s, pf);
-    for (int sp = 0; sp < 2; ++sp) {
-      const int o = 1 - sp;
-      K(TC_K_OTHER, fb * 7.0, [&] {
-        hipLaunchKernelGGL((k_gdiv2<R, N>), dim3(nblk(NR)), dim3(256), 0, s, rc, tHUp.p, tHUa.p,
-                           wk2.p + (8 + 3 * sp) * NR, wk2.p + (8 + 3 * o) * NR, wk.p);
-      });
-      fft3d_t<R, N>(wk.p, 1, +1, s, pf);
-      TC_HIP(hipMemcpyAsync(LOC[sp] + 5 * NR, wk.p, NR * sizeof(cx<R>), hipMemcpyDeviceToDevice, s));
-    }
-    ev.rec(2, s);
-
-    // ---- 2: occupied-occupied pass of each channel (h5 split by kernel channel)
-    const bool need_occ = m.m3a2 || m.m3a4 || m.m3b2 || m.m3b5;
-    const int chunk = (P + S - 1) / S;
-    for (int sp = 0; sp < 2; ++sp) {
-      TC_HIP(hipMemsetAsync(H3[sp], 0, size_t(3) * P * NR * sizeof(cx<R>), s));
-      TC_HIP(hipMemsetAsync(H5P[sp], 0, size_t(P) * NR * sizeof(R), s));
-      TC_HIP(hipMemsetAsync(H5A[sp], 0, size_t(P) * NR * sizeof(R), s));
-      if (bitc) {
-        TC_HIP(hipMemsetAsync(HBC[sp], 0, size_t(3) * P * NR * sizeof(cx<R>), s));
-        TC_HIP(hipMemsetAsync(H5C[sp], 0, size_t(P) * NR * sizeof(cx<R>), s));
-        TC_HIP(hipMemsetAsync(H5CA[sp], 0, size_t(P) * NR * sizeof(cx<R>), s));
-      }
-    }
-    if (need_occ) {
-      for (int s2 = 0; s2 < 2; ++s2)
-        for (int a0 = 0; a0 < P; a0 += T) {
-          const int nt = std::min(T, P - a0);
-          const long npair = long(nt) * P;
-          const FusedArgs fa{P, nt, a0, S, chunk};
-          if (bitc) {
-            // rho21 = conj(chi_a) psi_b and rho12 = conj(chi_b) psi_a of channel s2 (as in the unpolarised
-            // biorthogonal pass), h5 split by kernel channel
-            cx<R>* in12 = bufA.p + npair * NR;
-            cx<R>* out12 = bufB.p + 4 * npair * NR;
-            K(TC_K_XY_PAIR_OCC, fb * 2.0 * (npair + nt + P), [&] {
-              hipLaunchKernelGGL((k_pair_xy<R, N, true>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, XS[s2],
-                                 PSI[s2], fa, bufA.p);
-              hipLaunchKernelGGL((k_pair_xy<R, N, false>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, XS[s2],
-                                 PSI[s2], fa, in12);
-            });
-            K(TC_K_ZCONV_OCC, 2.0 * (fb * 5.0 * npair + tabB), [&] {
-              zconv<OP_O>(s, bufA.p, bufB.p, npair, a0, mi, tb, 0);
-              zconv<OP_O>(s, in12, out12, npair, a0, mi, tb, 1);
-            });
-            K(TC_K_FUSED_OB, fb * (8.0 * npair + 2.0 * P) + 8.0 * fb * nt * S, [&] {
-              hipLaunchKernelGGL((k_fused_OB<R, N, true>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, bufB.p, out12,
-                                 PSI[s2], XS[s2], W[s2], fa, mi, rc, dfr.p, h5cpart.p, H3part.p, Hbpart.p, -1L, 4L,
-                                 -1L, 4L);
-            });
-            K(TC_K_SUM_PARTS, 8.0 * fb * nt * (S + 1), [&] {
-              hipLaunchKernelGGL((k_sum_parts_ob<R, N>), dim3(nblk(long(nt) * NR)), dim3(256), 0, s, S, nt, a0,
-                                 h5cpart.p, H3part.p, Hbpart.p, H5C[s2], H3[s2], HBC[s2]);
-              hipLaunchKernelGGL((k_sum_cx_parts<R, N>), dim3(nblk(long(nt) * NR)), dim3(256), 0, s, S, nt, a0,
-                                 h5cpart.p + size_t(S) * nt * NR, H5CA[s2]);
-            });
-            continue;
-          }
-          K(TC_K_XY_PAIR_OCC, fb * (npair + nt + P), [&] {
-            hipLaunchKernelGGL((k_pair_xy<R, N, true>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, PSI[s2], PSI[s2],
-                               fa, bufA.p);
-          });
-          K(TC_K_ZCONV_OCC, fb * 5.0 * npair + tabB, [&] {
-            zconv<OP_O>(s, npair, a0, mi, tb, 0);
-          });
-          K(TC_K_FUSED_O, fb * (4.0 * npair + P) + 4.5 * fb * nt * S, [&] {
-            hipLaunchKernelGGL((k_fused_O<R, N, true>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, bufB.p, PSI[s2],
-                               W[s2], fa, mi, rc, dfr.p, h5part.p, H3part.p);
-          });
-          K(TC_K_SUM_PARTS, 5.0 * fb * nt * (S + 1), [&] {
-            hipLaunchKernelGGL((k_sum_parts<R, N>), dim3(nblk(long(nt) * NR)), dim3(256), 0, s, 0, S, nt, a0, 0,
-                               h5part.p, H3part.p, nullptr, nullptr, H5P[s2], H3[s2], nullptr, nullptr);
-            hipLaunchKernelGGL((k_sum_real_parts<R, N>), dim3(nblk(long(nt) * NR)), dim3(256), 0, s, S, nt, a0,
-                               h5part.p + size_t(S) * nt * NR, H5A[s2]);
-          });
-        }
-      // M_s2 = sum w conj(H3a4) psi per channel (3b2 sources), then h6 and the 3b2 field per target spin
-      for (int s2 = 0; s2 < 2; ++s2)
-        K(TC_K_OTHER, fb * (5.0 * P + 4.0), [&] {
-          if (bitc)
-            hipLaunchKernelGGL((k_reduce_occ<R, N, cx<R>>), dim3(nblk(NR)), dim3(256), 0, s, H5C[s2], HBC[s2],
-                               PSI[s2], W[s2], P, LOC[s2] + 6 * NR, wk2.p + (8 + 3 * s2) * NR);
-          else
-            hipLaunchKernelGGL((k_reduce_occ<R, N, R>), dim3(nblk(NR)), dim3(256), 0, s, H5P[s2], H3[s2], PSI[s2],
-                               W[s2], P, LOC[s2] + 6 * NR, wk2.p + (8 + 3 * s2) * NR);
-        });
-      fft3d_t<R, N>(wk2.p + 8 * NR, 6, -1, s, pf);
-      for (int sp = 0; sp < 2; ++sp) {
-        const int o = 1 - sp;
-        K(TC_K_OTHER, fb * (2.0 * P + 1.0), [&] {
-          if (bitc)
-            hipLaunchKernelGGL((k_h6_pol_c<R, N>), dim3(nblk(NR)), dim3(256), 0, s, H5C[sp], W[sp], H5CA[o], W[o], P,
-                               LOC[sp] + 6 * NR);
-          else
-            hipLaunchKernelGGL((k_h6_pol<R, N>), dim3(nblk(NR)), dim3(256), 0, s, H5P[sp], W[sp], H5A[o], W[o], P,
-                               LOC[sp] + 6 * NR);
-          hipLaunchKernelGGL((k_gdiv2<R, N>), dim3(nblk(NR)), dim3(256), 0, s, rc, tHUp.p, tHUa.p,
-                             wk2.p + (8 + 3 * sp) * NR, wk2.p + (8 + 3 * o) * NR, wk.p);
-        });
-        fft3d_t<R, N>(wk.p, 1, +1, s, pf);
-        TC_HIP(hipMemcpyAsync(LOC[sp] + 7 * NR, wk.p, NR * sizeof(cx<R>), hipMemcpyDeviceToDevice, s));
-      }
-    }
-    for (int sp = 0; sp < 2; ++sp)
-      K(TC_K_OTHER, 6.0 * fb * P, [&] {
-        hipLaunchKernelGGL((k_lattice3<R, N>), dim3(nblk(long(P) * NR)), dim3(256), 0, s, H3[sp], HL[sp], bm, long(P),
-                           3 * NR, NR);
-        if (bitc)   // in place: B conj(H3b), the pass-B partner field
-          hipLaunchKernelGGL((k_lattice3<R, N>), dim3(nblk(long(P) * NR)), dim3(256), 0, s, HBC[sp], HBC[sp], bm,
-                             long(P), 3 * NR, NR);
-      });
-    ev.rec(3, s);
-
-    // ---- 3/4: target batches of each spin (partners of the same spin)
-    const bool need_A = m.m2ax || m.m2bx1 || m.m2bx2 || m.m3a3 || m.m3a4 || m.m3b4 || m.m3b6;
-    const bool need_B = m.m2bx2 || m.m3b3 || m.m3b4 || m.m3b5;
-    for (int sp = 0; sp < 2; ++sp) {
-      const int o = 1 - sp;
-      const cx<R>* tP = PSI[sp];   // target fields: this channel's orbitals or trial vectors
-      const cx<R>* tD = DD[sp];
-      if (ts) {
-        TC_HIP(hipMemsetAsync(psiT.p, 0, size_t(NTG) * NR * sizeof(cx<R>), s));
-        TC_HIP(hipMemsetAsync(DT.p, 0, size_t(3) * NTG * NR * sizeof(cx<R>), s));
-        const unsigned gst = nblk(long(NTG) * npm);
-        const double* tc = ts->coef + sp * tcofs;
-        K(TC_K_SCATTER, 0.0, [&] {
-          hipLaunchKernelGGL((k_scatter<R>), dim3(gst), dim3(256), 0, s, tc, sh.boxidx.p, sh.npw.p, sh.kg.p, nbt, npm,
-                             NTG, -1, psiT.p, NR);
-          for (int c = 0; c < 3; ++c)
-            hipLaunchKernelGGL((k_scatter<R>), dim3(gst), dim3(256), 0, s, tc, sh.boxidx.p, sh.npw.p, sh.kg.p, nbt,
-                               npm, NTG, c, DT.p + size_t(c) * NTG * NR, NR);
-        });
-        fft3d_t<R, N>(psiT.p, NTG, +1, s, pf);
-        fft3d_t<R, N>(DT.p, 3L * NTG, +1, s, pf);
-        tP = psiT.p;
-        tD = DT.p;
-      }
-      for (int t0 = 0; t0 < NTG; t0 += T) {
-        const int nt = std::min(T, NTG - t0);
-        const long npair = long(nt) * P;
-        TC_HIP(hipMemsetAsync(acc.p, 0, size_t(kAccSlots) * T * NR * sizeof(cx<double>), s));
-        TC_HIP(hipMemsetAsync(h4.p, 0, size_t(3) * T * NR * sizeof(cx<R>), s));
-        Events bev(3);
-        bev.rec(0, s);
-        const double part = fb * nt * S;
-        if (need_A) {
-          const FusedArgs fa{P, nt, t0, S, chunk};
-          K(TC_K_XY_PAIR_TGT, fb * (npair + nt + P), [&] {
-            hipLaunchKernelGGL((k_pair_xy<R, N, false>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, XS[sp],
-                               tP, fa, bufA.p);
-          });
-          K(TC_K_ZCONV_A1, fb * 6.0 * npair + tabB, [&] {
-            zconv<OP_A1>(s, npair, t0, miT, tb, 1);
-          });
-          K(TC_K_FUSED_A, fb * ((m.m3b6 ? 9.0 : 5.0) * npair + 8.0 * P + nt) + 6.0 * part, [&] {
-            if (bitc)   // complex densities
-              hipLaunchKernelGGL((k_fused_A<R, N, true, true>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, bufB.p,
-                                 PSI[sp], DL[sp], HL[sp], NJ[sp], W[sp], fa, m, int(m.m3b6 != 0), miT, bm, mm, dfr.p,
-                                 bufA.p, gpart.p, h4part.p, NJ[o]);
-            else
-              hipLaunchKernelGGL((k_fused_A<R, N, true, false>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, bufB.p,
-                                 PSI[sp], DL[sp], HL[sp], NJ[sp], W[sp], fa, m, int(m.m3b6 != 0), miT, bm, mm, dfr.p,
-                                 bufA.p, gpart.p, h4part.p, NJ[o]);
-          });
-          K(TC_K_SUM_PARTS, 6.0 * part + 6.0 * fd * nt + 3.0 * fb * nt, [&] {
-            hipLaunchKernelGGL((k_sum_parts<R, N>), dim3(nblk(long(nt) * NR)), dim3(256), 0, s, 1, S, nt, t0, 0,
-                               nullptr, nullptr, gpart.p, h4part.p, nullptr, nullptr, acc.p, h4.p);
-          });
-          if (m.m3b6 && !need_B) {   // else shared with pass B below
-            K(TC_K_ZCONV_A2, fb * 5.0 * npair + tabB, [&] {
-              zconv<OP_A2>(s, npair, t0, miT, tb, 1);
-            });
-            K(TC_K_FUSED_Y, fb * (npair + P) + part, [&] {
-              hipLaunchKernelGGL((k_fused_Y<R, N>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, bufB.p, PSI[sp],
-                                 W[sp], fa, 1.0, gpart.p);
-            });
-            K(TC_K_SUM_PARTS, part + 2.0 * fd * nt, [&] {
-              hipLaunchKernelGGL((k_sum_parts<R, N>), dim3(nblk(long(nt) * NR)), dim3(256), 0, s, 2, S, nt, t0, 2,
-                                 nullptr, nullptr, gpart.p, nullptr, nullptr, nullptr, acc.p, nullptr);
-            });
-          }
-        }
-        bev.rec(1, s);
-        if (need_B) {
-          // 3b6 and pass B share one z stage and one partner sum (as in the unpolarised path)
-          const bool merged = need_A && m.m3b6;
-          const FusedArgs fy{P, nt, t0, S, chunk};
-          cx<R>* srcB = merged ? bufB.p : bufA.p;
-          cx<R>* zout = merged ? bufB.p + size_t(2) * npair * NR : bufB.p;
-          K(TC_K_OTHER, fb * 13.0 * nt, [&] {
-            hipLaunchKernelGGL((k_passB_Z<R, N>), dim3(nblk(long(nt) * NR)), dim3(256), 0, s, tP, tD,
-                               LOC[sp] + NR, h4.p, t0, nt, NTG, m, bm, Z.p);
-          });
-          K(TC_K_XY_PASSB, fb * (2.0 * npair + 4.0 * P + 4.0 * nt), [&] {
-            hipLaunchKernelGGL((k_passB_xy<R, N>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, tP, XS[sp], Z.p,
-                               bitc ? HBC[sp] : HL[sp], fy, miT, dfr.p, R(m.m3b5), srcB);
-          });
-          if (merged) {
-            K(TC_K_ZCONV_A2, fb * 7.0 * npair + tabB, [&] {
-              zconv<OP_A2>(s, bufA.p, zout, npair, t0, miT, tb, 1, bufB.p);
-            });
-          } else {
-            K(TC_K_ZCONV_B, fb * 3.0 * npair + tabB, [&] {
-              zconv<OP_B>(s, npair, t0, miT, tb, 1);
-            });
-          }
-          K(TC_K_FUSED_Y, fb * (npair + P) + part, [&] {
-            hipLaunchKernelGGL((k_fused_Y<R, N>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, zout, PSI[sp], W[sp],
-                               fy, 1.0, gpart.p);
-          });
-          K(TC_K_SUM_PARTS, part + 2.0 * fd * nt, [&] {
-            hipLaunchKernelGGL((k_sum_parts<R, N>), dim3(nblk(long(nt) * NR)), dim3(256), 0, s, 2, S, nt, t0, 3,
-                               nullptr, nullptr, gpart.p, nullptr, nullptr, nullptr, acc.p, nullptr);
-          });
-        }
-        bev.rec(2, s);
-        K(TC_K_OTHER, fb * 16.0 * nt + 8.0 * fd * nt, [&] {
-          hipLaunchKernelGGL((k_local<R, N>), dim3(nblk(long(nt) * NR)), dim3(256), 0, s, tP, tD, LOC[sp],
-                             h4.p, t0, nt, NTG, m, acc.p, g.p);
-          if (!ts)
-            hipLaunchKernelGGL((k_epart<R, N>), dim3(kAccSlots * nt), dim3(256), 0, s, XS[sp], acc.p, t0, nt,
-                               sh.epart.p + size_t(kAccSlots) * sp * P);
-        });
-        fft3d_t<R, N>(g.p, nt, -1, s, pf);
-        K(TC_K_OTHER, 0.0, [&] {
-          hipLaunchKernelGGL((k_gather<R>), dim3(nblk(long(nt) * npm)), dim3(256), 0, s, g.p, sh.boxidx.p, sh.npw.p,
-                             nbt, npm, t0, nt, 1.0 / double(NR), ts ? ts->out + sp * tcofs : sh.out.p + sp * cofs, NR);
-        });
-        bev.sync(2, s);
-        msA += bev.ms(0, 1);
-        msB += bev.ms(1, 2);
-      }
-    }
-    ev.rec(4, s);
-
-    // ---- 5: kinetic energy and FP64 corrections per channel
-    K(TC_K_CORR, 0.0, [&] {
-      if (!ts) {
-        for (int sp = 0; sp < 2; ++sp)
-          hipLaunchKernelGGL(k_kinetic, dim3(P), dim3(256), 0, s, (bitc ? sh.coefL.p : sh.coef.p) + sp * cofs,
-                             sh.coef.p + sp * cofs, sh.kg.p, sh.npw.p, nb, npm, sh.tkin.p + size_t(sp) * P);
-        TC_HIP(hipMemsetAsync(sh.ecorr.p, 0, size_t(4) * P * sizeof(double), s));
-      }
-      if (need_corr(pb, m)) corrections_pol(s, sh, pb, m, ts);
     });
     ev.rec(5, s);
     ev.sync(5, s);

@@ -380,3 +380,20 @@ def test_bitc_polarized_scf_with_equal_channels_follows_the_unpolarized_loop():
     _say(f"    energies {out[0]} vs {out[1]}")
     assert len(out[0]) == len(out[1])
     np.testing.assert_allclose(out[1], out[0], rtol=1e-10)
+
+
+@pytest.mark.parametrize("name", ["fcc_k221_g12_pol_empty_band", "fcc_k211_g8_bitc_pol"])
+def test_polarized_pair_store_on_and_off_agree(name):
+    """Two channels with the resident store of pass-A z-stage outputs (one region per channel, read by the
+    occupied pass and pass A) and without it (each pass forms its own pairs): the same operator."""
+    w = CASES[name]()
+    _say(f"[gpu] polarised {name}: pair store on / off")
+    res = []
+    for store in (True, False):
+        op = tc.from_workload(w, precision=tc.TC_PREC_FP64, pair_store=store)
+        res.append((op.apply(), op.energy()[0], op.orbital_energies()))
+        op.close()
+    for s in (0, 1):
+        assert relerr(res[1][0][s], res[0][0][s]) < 1e-12
+    assert abs(res[1][1] - res[0][1]) < 1e-12 * abs(res[0][1])
+    assert np.abs(res[1][2] - res[0][2]).max() < 1e-12 * np.abs(res[0][2]).max()
