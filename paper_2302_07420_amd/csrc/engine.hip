@@ -838,7 +838,6 @@ struct Engine {
   virtual void upload_tables(const Problem& pb, const TableVariant& tv) = 0;
   virtual void apply(hipStream_t s, Shared& sh, const Problem& pb, double* stage_ms,
                      const TargetSet* ts = nullptr) = 0;
-  virtual void apply_sym(hipStream_t s, Shared& sh, const Problem& pb, double* stage_ms) = 0;
   virtual void release_pair_store() = 0;
   Prof* prof = nullptr;
 };
@@ -1313,12 +1312,18 @@ struct EngineT : Engine {
   // channels the Hartree-type fields of target spin s take the parallel tables on its own density and the
   // antiparallel ones on the other's, exchange-type terms pair orbitals of one spin, and the occupied pass
   // keeps the parallel and antiparallel parts of h5 apart: h6 of spin s sums the first over own-spin rows
-  // and the second over other-spin rows.
+  // and the second over other-spin rows.  With crystal symmetry (TC mode, one channel) the rows of the
+  // occupied-occupied pass (q2 of Algs. 3a2, 3a4, 3b2) and the targets are the orbitals of the
+  // representative k-points only: h5 and H3a4 of the other orbitals follow from the representatives' by the
+  // grid permutation of their operation (k_sym_fields), their outputs and energy slots likewise (k_sym_coef,
+  // k_sym_epart); densities, partner sums and corrections use every orbital.
   void apply(hipStream_t s, Shared& sh, const Problem& pb, double* stage_ms, const TargetSet* ts) override {
     const int P = pb.P();
     const int nb = pb.nb;
     const int ns = pb.nspin;
     const bool pol = ns == 2;
+    const bool sym = pb.nsym > 0;   // TC mode, one channel, orbitals as targets (checked at preparation)
+    const int PI = sym ? int(pb.irr.size()) * nb : P;   // the representatives' orbitals
     Masks m = make_masks(pb.mask);
     if (pb.negate_b) {   // v2 -> v2^dagger: the grad-u . grad terms change sign (with the ADJOINT tables)
       m.m2bh1 = -m.m2bh1;
@@ -1335,13 +1340,14 @@ struct EngineT : Engine {
     // channel) it is computed once, before the occupied pass, which then reads it in place of its own pair
     // densities and z stage.  (The store is settled before the batch buffers, which take what it leaves of a
     // caller's budget.)
-    const bool keepA = !ts && need_occ && need_A && pair_store(pb);
+    const bool keepA = !ts && !sym && need_occ && need_A && pair_store(pb);
     ensure(pb, pair_budget(pb));
     // targets: the orbitals, or nbt trial vectors per k-point
     const int nbt = ts ? ts->nvec : nb;
-    const int NTG = (ts && ts->nblk ? ts->nblk : pb.nk) * nbt;
-    const MeshInfo mi{pb.n1, pb.n2, pb.n3, nb, P, nb};     // occupied-occupied pass
-    const MeshInfo miT{pb.n1, pb.n2, pb.n3, nb, P, nbt, ts ? ts->tk : nullptr, pb.nkb};   // target passes
+    const int NTG = sym ? PI : (ts && ts->nblk ? ts->nblk : pb.nk) * nbt;
+    // occupied-occupied pass and target passes (with symmetry: rows and targets are the representatives)
+    const MeshInfo mi = sym ? MeshInfo{pb.n1, pb.n2, pb.n3, nb, P, nb, sh.irrk.p} : MeshInfo{pb.n1, pb.n2, pb.n3, nb, P, nb};
+    const MeshInfo miT = sym ? mi : MeshInfo{pb.n1, pb.n2, pb.n3, nb, P, nbt, ts ? ts->tk : nullptr, pb.nkb};
     // plane-wave data of the targets (band targets carry their own)
     const bool tb_own = ts && ts->boxidx;
     const int* tbox = tb_own ? ts->boxidx : sh.boxidx.p;
@@ -1418,9 +1424,22 @@ struct EngineT : Engine {
     }
     // target fields of trial vectors or band orbitals (channel c's; with one channel made here, with two at
     // that channel's target passes)
-    if (ts) {
+    if (ts || sym) {
       psiT.alloc(size_t(NTG) * NR);
       DT.alloc(size_t(3) * NTG * NR);
+    }
+    if (sym) {   // the representatives' fields as rows and targets; their fields and outputs before expansion
+      for (int i = 0; i < int(pb.irr.size()); ++i) {
+        const size_t blk = size_t(nb) * NR, src = size_t(pb.irr[i]) * blk, dst = size_t(i) * blk;
+        TC_HIP(hipMemcpyAsync(psiT.p + dst, psi.p + src, blk * sizeof(cx<R>), hipMemcpyDeviceToDevice, s));
+        for (int d = 0; d < 3; ++d)
+          TC_HIP(hipMemcpyAsync(DT.p + size_t(d) * PI * NR + dst, D.p + size_t(d) * P * NR + src, blk * sizeof(cx<R>),
+                                hipMemcpyDeviceToDevice, s));
+      }
+      H3I.alloc(size_t(3) * PI * NR);
+      h5I.alloc(size_t(PI) * NR);
+      sh.outI.alloc(size_t(2) * PI * pb.npw_max);
+      sh.epartI.alloc(size_t(kAccSlots) * PI);
     }
     auto scatter_targets = [&](int c) {
       TC_HIP(hipMemsetAsync(psiT.p, 0, size_t(NTG) * NR * sizeof(cx<R>), s));
@@ -1524,6 +1543,7 @@ struct EngineT : Engine {
     for (int c = 0; c < ns; ++c) {
       TC_HIP(hipMemsetAsync(H3[c], 0, size_t(3) * P * NR * sizeof(cx<R>), s));
       if (bitc) TC_HIP(hipMemsetAsync(HBC[c], 0, size_t(3) * P * NR * sizeof(cx<R>), s));
+      if (sym) TC_HIP(hipMemsetAsync(h5.p, 0, size_t(P) * NR * sizeof(R), s));
       if (pol && bitc) {
         TC_HIP(hipMemsetAsync(H5C[c], 0, size_t(P) * NR * sizeof(cx<R>), s));
         TC_HIP(hipMemsetAsync(H5CA[c], 0, size_t(P) * NR * sizeof(cx<R>), s));
@@ -1534,8 +1554,8 @@ struct EngineT : Engine {
     }
     if (need_occ) {
       for (int c = 0; c < ns; ++c)
-        for (int a0 = 0; a0 < P; a0 += T) {
-          const int nt = std::min(T, P - a0);
+        for (int a0 = 0; a0 < PI; a0 += T) {
+          const int nt = std::min(T, PI - a0);
           const long npair = long(nt) * P;
           const FusedArgs fa{P, nt, a0, S, chunk};
           if (bitc) {
@@ -1593,8 +1613,8 @@ struct EngineT : Engine {
               sQ = 5L * P;
             } else {
               K(TC_K_XY_PAIR_OCC, fb * (npair + nt + P), [&] {
-                hipLaunchKernelGGL((k_pair_xy<R, N, true>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, PSI[c],
-                                   PSI[c], fa, bufA.p);
+                hipLaunchKernelGGL((k_pair_xy<R, N, true>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s,
+                                   sym ? psiT.p : PSI[c], PSI[c], fa, bufA.p);
               });
               K(TC_K_ZCONV_OCC, fb * 5.0 * npair + tabB, [&] {
                 zconv<OP_O>(s, npair, a0, mi, tb, 0);
@@ -1610,13 +1630,19 @@ struct EngineT : Engine {
             });
             K(TC_K_SUM_PARTS, (pol ? 5.0 : 4.0) * fb * nt * (S + 1), [&] {
               hipLaunchKernelGGL((k_sum_parts<R, N>), dim3(nblk(long(nt) * NR)), dim3(256), 0, s, 0, S, nt, a0, 0,
-                                 h5part.p, H3part.p, nullptr, nullptr, H5P[c], H3[c], nullptr, nullptr);
+                                 h5part.p, H3part.p, nullptr, nullptr, sym ? h5I.p : H5P[c], sym ? H3I.p : H3[c],
+                                 nullptr, nullptr);
               if (pol)   // the antiparallel-channel part (second half of the partials)
                 hipLaunchKernelGGL((k_sum_real_parts<R, N>), dim3(nblk(long(nt) * NR)), dim3(256), 0, s, S, nt, a0,
                                    h5part.p + size_t(S) * nt * NR, H5A[c]);
             });
           }
         }
+      if (sym)   // every orbital's h5 and H3a4 from its representative's
+        K(TC_K_OTHER, fb * 4.0 * (P + PI), [&] {
+          hipLaunchKernelGGL((k_sym_fields<R, N>), dim3(nblk(long(P) * NR)), dim3(256), 0, s, sh.symk.p, nb, P, h5I.p,
+                             H3I.p, h5.p, H3a4.p);
+        });
       // h6 = sum w h5, M = sum w conj(H3c) psi (the 3b2 sources) and the 3b2 field
       if (!pol) {
         K(TC_K_OTHER, fb * (5.0 * P + 4.0), [&] {
@@ -1696,8 +1722,8 @@ struct EngineT : Engine {
     for (int c = 0; c < ns; ++c) {
       const int o = pol ? 1 - c : 0;
       if (ts && pol) scatter_targets(c);
-      const cx<R>* tP = ts ? psiT.p : PSI[c];   // target fields
-      const cx<R>* tD = ts ? DT.p : DD[c];
+      const cx<R>* tP = (ts || sym) ? psiT.p : PSI[c];   // target fields
+      const cx<R>* tD = (ts || sym) ? DT.p : DD[c];
       for (int t0 = 0; t0 < NTG; t0 += T) {
         const int nt = std::min(T, NTG - t0);
         const long npair = long(nt) * P;
@@ -1807,17 +1833,26 @@ struct EngineT : Engine {
           hipLaunchKernelGGL((k_local<R, N>), dim3(nblk(long(nt) * NR)), dim3(256), 0, s, tP, tD, LOC[c], h4.p, t0, nt,
                              NTG, m, acc.p, g.p);
           if (!ts)
-            hipLaunchKernelGGL((k_epart<R, N>), dim3(kAccSlots * nt), dim3(256), 0, s, XS[c], acc.p, t0, nt,
-                               sh.epart.p + size_t(kAccSlots) * c * P);
+            hipLaunchKernelGGL((k_epart<R, N>), dim3(kAccSlots * nt), dim3(256), 0, s, sym ? psiT.p : XS[c], acc.p, t0,
+                               nt, sym ? sh.epartI.p : sh.epart.p + size_t(kAccSlots) * c * P);
         });
         fft3d_t<R, N>(g.p, nt, -1, s, pf);
         K(TC_K_OTHER, 0.0, [&] {
           hipLaunchKernelGGL((k_gather<R>), dim3(nblk(long(nt) * tnpm)), dim3(256), 0, s, g.p, tbox, tnpw, nbt, tnpm,
-                             t0, nt, 1.0 / double(NR), (ts ? ts->out + c * tcofs : sh.out.p + c * cofs), NR);
+                             t0, nt, 1.0 / double(NR),
+                             (ts ? ts->out + c * tcofs : sym ? sh.outI.p : sh.out.p + c * cofs), NR,
+                             sym ? sh.irrk.p : nullptr);
         });
       }
     }
     if (ts && ts->OBh4) band_grid(s, sh, pb, *ts, NTG, psiT.p, tbox, tnpw, tkg, tnpm, rc);
+    if (sym)   // every orbital's output and energy slots from its representative's
+      K(TC_K_OTHER, 0.0, [&] {
+        hipLaunchKernelGGL(k_sym_coef, dim3(nblk(long(P) * pb.npw_max)), dim3(256), 0, s, sh.symk.p, sh.symg0.p,
+                           sh.symph.p, sh.npw.p, pb.nk, nb, pb.npw_max, sh.outI.p, sh.out.p);
+        hipLaunchKernelGGL(k_sym_epart, dim3(nblk(long(P) * kAccSlots)), dim3(256), 0, s, sh.symk.p, nb, P, kAccSlots,
+                           sh.epartI.p, sh.epart.p);
+      });
     ev.rec(4, s);
 
     // ---- 5: kinetic energy and FP64 corrections
@@ -1918,264 +1953,6 @@ struct EngineT : Engine {
     fft3d_t<double, N>(prodT.p, NTG, -1, s);
     hipLaunchKernelGGL((k_gather<double>), dim3(nblk(long(NTG) * tnpm)), dim3(256), 0, s, prodT.p, tbox, tnpw, nb,
                        tnpm, 0, NTG, 1.0 / double(NR), ts.X6, NR);
-  }
-
-  // Application with crystal symmetry (TC mode, one spin channel): the occupied-occupied rows (q2 of
-  // Algs. 3a2, 3a4, 3b2) and the targets are the orbitals of the representative k-points only.  h5 and
-  // H3a4 of the other orbitals follow from the representatives' by the grid permutation of their
-  // operation (k_sym_fields); the outputs and energy slots of the other orbitals from the
-  // representatives' (k_sym_coef, k_sym_epart).  Densities, partner sums and corrections use every
-  // orbital.
-  void apply_sym(hipStream_t s, Shared& sh, const Problem& pb, double* stage_ms) override {
-    const int P = pb.P();
-    const int nb = pb.nb;
-    const int npm = pb.npw_max;
-    const int nirr = int(pb.irr.size());
-    const int PI = nirr * nb;
-    const Masks m = make_masks(pb.mask);
-    ensure(pb, pair_budget(pb));
-    const MeshInfo mi{pb.n1, pb.n2, pb.n3, nb, P, nb, sh.irrk.p};   // rows / targets: representatives
-    Recip rc;
-    for (int i = 0; i < 9; ++i) rc.b[i] = pb.B[i];
-    Basis<R> bm, mm;
-    for (int i = 0; i < 9; ++i) bm.b[i] = R(pb.B[i]);
-    for (int d = 0; d < 3; ++d)
-      for (int e = 0; e < 3; ++e)
-        mm.b[3 * d + e] = R(pb.B[3 * d] * pb.B[3 * e] + pb.B[3 * d + 1] * pb.B[3 * e + 1] + pb.B[3 * d + 2] * pb.B[3 * e + 2]);
-    const Tables tb{tV.p, tU1.p, tU2.p, dfr.p};
-    const double fb = double(sizeof(cx<R>)) * NR;
-    const double fd = double(sizeof(cx<double>)) * NR;
-    const double tabB = 3.0 * double(sizeof(R)) * NR * double((2 * pb.n1 - 1) * (2 * pb.n2 - 1) * (2 * pb.n3 - 1));
-    Prof* pf = prof;
-    auto K = [&](int id, double bytes, auto&& launch) {
-      ProfScope ps(pf, s, id, bytes);
-      launch();
-    };
-    psiT.alloc(size_t(PI) * NR);
-    DT.alloc(size_t(3) * PI * NR);
-    H3I.alloc(size_t(3) * PI * NR);
-    h5I.alloc(size_t(PI) * NR);
-    sh.outI.alloc(size_t(2) * PI * npm);
-    sh.epartI.alloc(size_t(kAccSlots) * PI);
-    Events ev(6);
-    double msA = 0, msB = 0;
-    ev.rec(0, s);
-
-    // ---- 0: G -> r of every orbital; the representatives' fields as targets
-    TC_HIP(hipMemsetAsync(psi.p, 0, size_t(P) * NR * sizeof(cx<R>), s));
-    TC_HIP(hipMemsetAsync(D.p, 0, size_t(3) * P * NR * sizeof(cx<R>), s));
-    const unsigned gsc = nblk(long(P) * npm);
-    K(TC_K_SCATTER, 0.0, [&] {
-      hipLaunchKernelGGL((k_scatter<R>), dim3(gsc), dim3(256), 0, s, sh.coef.p, sh.boxidx.p, sh.npw.p, sh.kg.p, nb,
-                         npm, P, -1, psi.p, NR);
-      for (int c = 0; c < 3; ++c)
-        hipLaunchKernelGGL((k_scatter<R>), dim3(gsc), dim3(256), 0, s, sh.coef.p, sh.boxidx.p, sh.npw.p, sh.kg.p, nb,
-                           npm, P, c, D.p + size_t(c) * P * NR, NR);
-    });
-    fft3d_t<R, N>(psi.p, P, +1, s, pf);
-    fft3d_t<R, N>(D.p, 3L * P, +1, s, pf);
-    for (int i = 0; i < nirr; ++i) {
-      const size_t blk = size_t(nb) * NR, src = size_t(pb.irr[i]) * blk, dst = size_t(i) * blk;
-      TC_HIP(hipMemcpyAsync(psiT.p + dst, psi.p + src, blk * sizeof(cx<R>), hipMemcpyDeviceToDevice, s));
-      for (int c = 0; c < 3; ++c)
-        TC_HIP(hipMemcpyAsync(DT.p + size_t(c) * PI * NR + dst, D.p + size_t(c) * P * NR + src, blk * sizeof(cx<R>),
-                              hipMemcpyDeviceToDevice, s));
-    }
-    K(TC_K_OTHER, 6.0 * fb * P, [&] {
-      hipLaunchKernelGGL((k_lattice3<R, N>), dim3(nblk(long(P) * NR)), dim3(256), 0, s, D.p, Dl.p, bm, long(P), NR,
-                         long(P) * NR);
-    });
-    ev.rec(1, s);
-
-    // ---- 1: densities and Hartree-type fields (every orbital)
-    TC_HIP(hipMemsetAsync(loc.p, 0, 8 * NR * sizeof(cx<R>), s));
-    K(TC_K_OTHER, fb * (4.0 * P + 4.0), [&] {
-      hipLaunchKernelGGL((k_density<R, N>), dim3(nblk(NR)), dim3(256), 0, s, psi.p, psi.p, D.p, sh.w.p, P, nJ.p,
-                         nJ.p + NR);
-    });
-    TC_HIP(hipMemcpyAsync(wk.p, nJ.p, 4 * NR * sizeof(cx<R>), hipMemcpyDeviceToDevice, s));
-    fft3d_t<R, N>(wk.p, 4, -1, s, pf);
-    K(TC_K_OTHER, fb * 9.0, [&] {
-      hipLaunchKernelGGL((k_hartree_g<R, N>), dim3(nblk(NR)), dim3(256), 0, s, rc, tHV.p, tHU.p, wk.p, wk.p + NR,
-                         wk.p + 4 * NR);
-    });
-    fft3d_t<R, N>(wk.p + 4 * NR, 5, +1, s, pf);
-    TC_HIP(hipMemcpyAsync(loc.p, wk.p + 4 * NR, 5 * NR * sizeof(cx<R>), hipMemcpyDeviceToDevice, s));
-    K(TC_K_OTHER, fb * 7.0, [&] {
-      hipLaunchKernelGGL((k_mul_vec_scalar<R, N>), dim3(nblk(NR)), dim3(256), 0, s, loc.p + NR, nJ.p, wk.p);
-    });
-    fft3d_t<R, N>(wk.p, 3, -1, s, pf);
-    K(TC_K_OTHER, fb * 4.0, [&] {
-      hipLaunchKernelGGL((k_gdiv<R, N>), dim3(nblk(NR)), dim3(256), 0, s, rc, tHU.p, wk.p, wk.p + 3 * NR);
-    });
-    fft3d_t<R, N>(wk.p + 3 * NR, 1, +1, s, pf);
-    TC_HIP(hipMemcpyAsync(loc.p + 5 * NR, wk.p + 3 * NR, NR * sizeof(cx<R>), hipMemcpyDeviceToDevice, s));
-    ev.rec(2, s);
-
-    // ---- 2: occupied-occupied pass with the representatives' orbitals as rows, then the images
-    const bool need_occ = m.m3a2 || m.m3a4 || m.m3b2 || m.m3b5;
-    const int chunk = (P + S - 1) / S;
-    TC_HIP(hipMemsetAsync(H3a4.p, 0, size_t(3) * P * NR * sizeof(cx<R>), s));
-    TC_HIP(hipMemsetAsync(h5.p, 0, size_t(P) * NR * sizeof(R), s));
-    if (need_occ) {
-      for (int a0 = 0; a0 < PI; a0 += T) {
-        const int nt = std::min(T, PI - a0);
-        const long npair = long(nt) * P;
-        const FusedArgs fa{P, nt, a0, S, chunk};
-        K(TC_K_XY_PAIR_OCC, fb * (npair + nt + P), [&] {
-          hipLaunchKernelGGL((k_pair_xy<R, N, true>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, psiT.p, psi.p, fa,
-                             bufA.p);
-        });
-        K(TC_K_ZCONV_OCC, fb * 5.0 * npair + tabB, [&] {
-          zconv<OP_O>(s, npair, a0, mi, tb, 0);
-        });
-        K(TC_K_FUSED_O, fb * (4.0 * npair + P) + 3.5 * fb * nt * S, [&] {
-          hipLaunchKernelGGL((k_fused_O<R, N>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, bufB.p, psi.p, sh.w.p,
-                             fa, mi, rc, dfr.p, h5part.p, H3part.p);
-        });
-        K(TC_K_SUM_PARTS, 4.0 * fb * nt * (S + 1), [&] {
-          hipLaunchKernelGGL((k_sum_parts<R, N>), dim3(nblk(long(nt) * NR)), dim3(256), 0, s, 0, S, nt, a0, 0,
-                             h5part.p, H3part.p, nullptr, nullptr, h5I.p, H3I.p, nullptr, nullptr);
-        });
-      }
-      K(TC_K_OTHER, fb * 4.0 * (P + PI), [&] {
-        hipLaunchKernelGGL((k_sym_fields<R, N>), dim3(nblk(long(P) * NR)), dim3(256), 0, s, sh.symk.p, nb, P, h5I.p,
-                           H3I.p, h5.p, H3a4.p);
-      });
-      K(TC_K_OTHER, fb * (5.0 * P + 4.0), [&] {
-        hipLaunchKernelGGL((k_reduce_occ<R, N, R>), dim3(nblk(NR)), dim3(256), 0, s, h5.p, H3a4.p, psi.p, sh.w.p, P,
-                           loc.p + 6 * NR, wk.p);
-      });
-      fft3d_t<R, N>(wk.p, 3, -1, s, pf);
-      K(TC_K_OTHER, fb * 4.0, [&] {
-        hipLaunchKernelGGL((k_gdiv<R, N>), dim3(nblk(NR)), dim3(256), 0, s, rc, tHU.p, wk.p, wk.p + 3 * NR);
-      });
-      fft3d_t<R, N>(wk.p + 3 * NR, 1, +1, s, pf);
-      TC_HIP(hipMemcpyAsync(loc.p + 7 * NR, wk.p + 3 * NR, NR * sizeof(cx<R>), hipMemcpyDeviceToDevice, s));
-    }
-    K(TC_K_OTHER, 6.0 * fb * P, [&] {
-      hipLaunchKernelGGL((k_lattice3<R, N>), dim3(nblk(long(P) * NR)), dim3(256), 0, s, H3a4.p, Hl.p, bm, long(P),
-                         3 * NR, NR);
-    });
-    ev.rec(3, s);
-
-    // ---- 3/4: the representatives' orbitals as targets (partners: every orbital)
-    const bool need_A = m.m2ax || m.m2bx1 || m.m2bx2 || m.m3a3 || m.m3a4 || m.m3b4 || m.m3b6;
-    const bool need_B = m.m2bx2 || m.m3b3 || m.m3b4 || m.m3b5;
-    for (int t0 = 0; t0 < PI; t0 += T) {
-      const int nt = std::min(T, PI - t0);
-      const long npair = long(nt) * P;
-      TC_HIP(hipMemsetAsync(acc.p, 0, size_t(kAccSlots) * T * NR * sizeof(cx<double>), s));
-      TC_HIP(hipMemsetAsync(h4.p, 0, size_t(3) * T * NR * sizeof(cx<R>), s));
-      Events bev(3);
-      bev.rec(0, s);
-      const double part = fb * nt * S;
-      if (need_A) {
-        const FusedArgs fa{P, nt, t0, S, chunk};
-        K(TC_K_XY_PAIR_TGT, fb * (npair + nt + P), [&] {
-          hipLaunchKernelGGL((k_pair_xy<R, N, false>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, psi.p, psiT.p, fa,
-                             bufA.p);
-        });
-        K(TC_K_ZCONV_A1, fb * 6.0 * npair + tabB, [&] {
-          zconv<OP_A1>(s, npair, t0, mi, tb, 1);
-        });
-        K(TC_K_FUSED_A, fb * ((m.m3b6 ? 9.0 : 5.0) * npair + 8.0 * P + nt) + 6.0 * part, [&] {
-          hipLaunchKernelGGL((k_fused_A<R, N, false, false>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, bufB.p,
-                             psi.p, Dl.p, Hl.p, nJ.p, sh.w.p, fa, m, int(m.m3b6 != 0), mi, bm, mm, dfr.p, bufA.p,
-                             gpart.p, h4part.p);
-        });
-        K(TC_K_SUM_PARTS, 6.0 * part + 6.0 * fd * nt + 3.0 * fb * nt, [&] {
-          hipLaunchKernelGGL((k_sum_parts<R, N>), dim3(nblk(long(nt) * NR)), dim3(256), 0, s, 1, S, nt, t0, 0, nullptr,
-                             nullptr, gpart.p, h4part.p, nullptr, nullptr, acc.p, h4.p);
-        });
-        if (m.m3b6 && !need_B) {   // else shared with pass B below
-          K(TC_K_ZCONV_A2, fb * 5.0 * npair + tabB, [&] {
-            zconv<OP_A2>(s, npair, t0, mi, tb, 1);
-          });
-          K(TC_K_FUSED_Y, fb * (npair + P) + part, [&] {
-            hipLaunchKernelGGL((k_fused_Y<R, N>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, bufB.p, psi.p, sh.w.p,
-                               fa, 1.0, gpart.p);
-          });
-          K(TC_K_SUM_PARTS, part + 2.0 * fd * nt, [&] {
-            hipLaunchKernelGGL((k_sum_parts<R, N>), dim3(nblk(long(nt) * NR)), dim3(256), 0, s, 2, S, nt, t0, 2,
-                               nullptr, nullptr, gpart.p, nullptr, nullptr, nullptr, acc.p, nullptr);
-          });
-        }
-      }
-      bev.rec(1, s);
-      if (need_B) {
-        // 3b6 and pass B share one z stage and one partner sum (as in the unreduced path)
-        const bool merged = need_A && m.m3b6;
-        const FusedArgs fy{P, nt, t0, S, chunk};
-        cx<R>* srcB = merged ? bufB.p : bufA.p;
-        cx<R>* zout = merged ? bufB.p + size_t(2) * npair * NR : bufB.p;
-        K(TC_K_OTHER, fb * 13.0 * nt, [&] {
-          hipLaunchKernelGGL((k_passB_Z<R, N>), dim3(nblk(long(nt) * NR)), dim3(256), 0, s, psiT.p, DT.p, loc.p + NR,
-                             h4.p, t0, nt, PI, m, bm, Z.p);
-        });
-        K(TC_K_XY_PASSB, fb * (2.0 * npair + 4.0 * P + 4.0 * nt), [&] {
-          hipLaunchKernelGGL((k_passB_xy<R, N>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, psiT.p, psi.p, Z.p, Hl.p,
-                             fy, mi, dfr.p, R(m.m3b5), srcB);
-        });
-        if (merged) {
-          K(TC_K_ZCONV_A2, fb * 7.0 * npair + tabB, [&] {
-            zconv<OP_A2>(s, bufA.p, zout, npair, t0, mi, tb, 1, bufB.p);
-          });
-        } else {
-          K(TC_K_ZCONV_B, fb * 3.0 * npair + tabB, [&] {
-            zconv<OP_B>(s, npair, t0, mi, tb, 1);
-          });
-        }
-        K(TC_K_FUSED_Y, fb * (npair + P) + part, [&] {
-          hipLaunchKernelGGL((k_fused_Y<R, N>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, zout, psi.p, sh.w.p,
-                             fy, 1.0, gpart.p);
-        });
-        K(TC_K_SUM_PARTS, part + 2.0 * fd * nt, [&] {
-          hipLaunchKernelGGL((k_sum_parts<R, N>), dim3(nblk(long(nt) * NR)), dim3(256), 0, s, 2, S, nt, t0, 3, nullptr,
-                             nullptr, gpart.p, nullptr, nullptr, nullptr, acc.p, nullptr);
-        });
-      }
-      bev.rec(2, s);
-      K(TC_K_OTHER, fb * 16.0 * nt + 8.0 * fd * nt, [&] {
-        hipLaunchKernelGGL((k_local<R, N>), dim3(nblk(long(nt) * NR)), dim3(256), 0, s, psiT.p, DT.p, loc.p, h4.p, t0,
-                           nt, PI, m, acc.p, g.p);
-        hipLaunchKernelGGL((k_epart<R, N>), dim3(kAccSlots * nt), dim3(256), 0, s, psiT.p, acc.p, t0, nt,
-                           sh.epartI.p);
-      });
-      fft3d_t<R, N>(g.p, nt, -1, s, pf);
-      K(TC_K_OTHER, 0.0, [&] {
-        hipLaunchKernelGGL((k_gather<R>), dim3(nblk(long(nt) * npm)), dim3(256), 0, s, g.p, sh.boxidx.p, sh.npw.p, nb,
-                           npm, t0, nt, 1.0 / double(NR), sh.outI.p, NR, sh.irrk.p);
-      });
-      bev.sync(2, s);
-      msA += bev.ms(0, 1);
-      msB += bev.ms(1, 2);
-    }
-    // every orbital's output and energy slots from its representative's
-    K(TC_K_OTHER, 0.0, [&] {
-      hipLaunchKernelGGL(k_sym_coef, dim3(nblk(long(P) * npm)), dim3(256), 0, s, sh.symk.p, sh.symg0.p, sh.symph.p,
-                         sh.npw.p, pb.nk, nb, npm, sh.outI.p, sh.out.p);
-      hipLaunchKernelGGL(k_sym_epart, dim3(nblk(long(P) * kAccSlots)), dim3(256), 0, s, sh.symk.p, nb, P, kAccSlots,
-                         sh.epartI.p, sh.epart.p);
-    });
-    ev.rec(4, s);
-
-    // ---- 5: kinetic energy and FP64 corrections (every orbital)
-    K(TC_K_CORR, 0.0, [&] {
-      hipLaunchKernelGGL(k_kinetic, dim3(P), dim3(256), 0, s, sh.coef.p, sh.coef.p, sh.kg.p, sh.npw.p, nb, npm,
-                         sh.tkin.p);
-      TC_HIP(hipMemsetAsync(sh.ecorr.p, 0, size_t(2) * P * sizeof(double), s));
-      if (need_corr(pb, m)) corrections(s, sh, pb, m, nullptr);
-    });
-    ev.rec(5, s);
-    ev.sync(5, s);
-    if (pf && pf->on) pf->collect();
-    stage_ms[0] = ev.ms(0, 1);
-    stage_ms[1] = ev.ms(1, 2);
-    stage_ms[2] = ev.ms(2, 3);
-    stage_ms[3] = msA;
-    stage_ms[4] = msB;
-    stage_ms[5] = ev.ms(3, 5) - msA - msB;
   }
 
   // Spin-polarised SCF-mesh corrections (FP64): for target spin sp, 2ax with its own channel's overlaps;
@@ -3345,10 +3122,7 @@ void run_apply(tc_ctx* c, void* out_dev, double* out_host) {
   const int P = pb.nspin * pb.P();   // orbitals of all spin channels (spin-major)
   alloc_shared(c);
   c->eng->prof = t_arena ? nullptr : &c->prof;
-  if (pb.nsym > 0)
-    c->eng->apply_sym(c->stream, sh, pb, c->stage_ms);
-  else
-    c->eng->apply(c->stream, sh, pb, c->stage_ms);
+  c->eng->apply(c->stream, sh, pb, c->stage_ms);
   c->total_ms = 0;
   for (double v : c->stage_ms) c->total_ms += v;
   for (int sp = 0; sp < pb.nspin; ++sp) {
