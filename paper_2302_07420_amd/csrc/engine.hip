@@ -1173,34 +1173,47 @@ struct EngineT : Engine {
     return size_t(pb.P()) * ((pb.bitc ? 8 : 5) + 4) * NR * sizeof(cx<R>);
   }
 
-  // The resident store of pass-A z-stage outputs.  Without a caller budget: allocated when it leaves a
-  // quarter of the device (at least 16 GiB) free.  With one (tc_set_memory_budget): when the store and
-  // a batch of 8 targets fit in it.  Released when it does not fit; never under the no-allocation scratch.
-  bool pair_store(const Problem& pb) {
-    const size_t need = size_t(5) * pb.nspin * pb.P() * pb.P() * NR;   // one region per spin channel
-    if (t_arena) return false;
-    if (!pb.pair_store) {
+  // The resident store of pass-A z-stage outputs: the pairs (t, q) of every target t and of the first Q1
+  // partners q, [t][Q1][5] fields per spin channel.  Q1 = P when every pair fits; fewer partner columns when
+  // only part of them does (TC mode: the occupied pass reads the store for its rows a < Q1 and forms its
+  // own pairs for the others; the biorthogonal occupied pass needs the pairs of both orders, so there the
+  // store holds every pair or none).  Without a caller budget it may take what leaves a quarter of the
+  // device (at least 16 GiB) free, the store it already holds counted as free; with a budget
+  // (tc_set_memory_budget), what leaves a batch of 8 targets of pair buffers.  Fewer than an eighth of the
+  // columns are not worth the split passes: no store then.  Never under the no-allocation scratch.
+  // Returns Q1 (0: no store).
+  int pair_store(const Problem& pb) {
+    const int P = pb.P();
+    if (t_arena) return 0;
+    auto none = [&] {
       allB.release();
-      return false;
-    }
-    const size_t bytes = need * sizeof(cx<R>);
-    if (pb.mem_budget && bytes + per_target_bytes(pb) * std::min(8, pb.P()) > pb.mem_budget) {
-      allB.release();
-      return false;
-    }
-    if (allB.n >= need) return true;
-    allB.release();
-    if (!pb.mem_budget) {
+      return 0;
+    };
+    if (!pb.pair_store || P == 0) return none();
+    const size_t col = size_t(5) * pb.nspin * P * NR * sizeof(cx<R>);   // bytes of one partner column
+    size_t avail = 0;
+    if (pb.mem_budget) {
+      const size_t keep = per_target_bytes(pb) * std::min(8, P);
+      avail = pb.mem_budget > keep ? pb.mem_budget - keep : 0;
+    } else {
       size_t fr = 0, tot = 0;
-      if (hipMemGetInfo(&fr, &tot) != hipSuccess) return false;
-      if (bytes + std::max<size_t>(tot / 4, size_t(16) << 30) > fr) return false;
+      if (hipMemGetInfo(&fr, &tot) != hipSuccess) return none();
+      const size_t have = allB.p ? allB.n * sizeof(cx<R>) : 0;
+      const size_t reserve = std::max<size_t>(tot / 4, size_t(16) << 30);
+      avail = fr + have > reserve ? fr + have - reserve : 0;
     }
+    int q1 = int(std::min<size_t>(size_t(P), avail / col));
+    if (pb.bitc && q1 < P) q1 = 0;
+    if (q1 < (P + 7) / 8) return none();
+    const size_t need = col / sizeof(cx<R>) * q1;
+    if (allB.n >= need) return q1;
+    allB.release();
     try {
       allB.alloc(need);
     } catch (const TcError&) {
-      return false;
+      return 0;
     }
-    return true;
+    return q1;
   }
 
   // Bytes of per-batch pair buffers.  Without a caller budget: an eighth of the device's memory, between
@@ -1340,7 +1353,8 @@ struct EngineT : Engine {
     // channel) it is computed once, before the occupied pass, which then reads it in place of its own pair
     // densities and z stage.  (The store is settled before the batch buffers, which take what it leaves of a
     // caller's budget.)
-    const bool keepA = !ts && !sym && need_occ && need_A && pair_store(pb);
+    const int Q1 = (!ts && !sym && need_occ && need_A) ? pair_store(pb) : 0;   // stored partner columns
+    const bool keepA = Q1 > 0;
     ensure(pb, pair_budget(pb));
     // targets: the orbitals, or nbt trial vectors per k-point
     const int nbt = ts ? ts->nvec : nb;
@@ -1382,8 +1396,8 @@ struct EngineT : Engine {
     const double* W[2] = {sh.w.p, sh.w.p + P};
     const size_t cofs = size_t(2) * P * pb.npw_max;   // doubles per channel of the coefficients
     const size_t tcofs = size_t(2) * NTG * tnpm;      // doubles per channel of the target coefficients
-    // the resident store of channel c: [P][P][5][N^3] pass-A z-stage outputs, pair-major in target order
-    auto store = [&](int c) { return allB.p + size_t(c) * P * P * 5 * NR; };
+    // the resident store of channel c: [P][Q1][5][N^3] pass-A z-stage outputs, pair-major in target order
+    auto store = [&](int c) { return allB.p + size_t(c) * P * Q1 * 5 * NR; };
     // algorithmic bytes: fields each launch must read or write once (working precision)
     const double fb = double(sizeof(cx<R>)) * NR;
     const double fd = double(sizeof(cx<double>)) * NR;
@@ -1525,18 +1539,20 @@ struct EngineT : Engine {
 
     // ---- 2: occupied-occupied pair pass (Algs. 3a2, 3a4 and 3b2/3b5 first loops), per channel
     const int chunk = (P + S - 1) / S;
-    if (keepA) {
+    if (keepA) {   // the pairs (t, q < Q1) of every target, before the occupied pass
+      const MeshInfo miQ{pb.n1, pb.n2, pb.n3, nb, Q1, nb};
+      const int chunkQ = (Q1 + S - 1) / S;
       for (int c = 0; c < ns; ++c)
         for (int t0 = 0; t0 < P; t0 += T) {
           const int nt = std::min(T, P - t0);
-          const long npair = long(nt) * P;
-          const FusedArgs fa{P, nt, t0, S, chunk};
-          K(TC_K_XY_PAIR_TGT, fb * (npair + nt + P), [&] {
+          const long npair = long(nt) * Q1;
+          const FusedArgs fa{Q1, nt, t0, S, chunkQ};
+          K(TC_K_XY_PAIR_TGT, fb * (npair + nt + Q1), [&] {
             hipLaunchKernelGGL((k_pair_xy<R, N, false>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, XS[c], PSI[c],
                                fa, bufA.p);
           });
           K(TC_K_ZCONV_A1, fb * 6.0 * npair + tabB, [&] {
-            zconv<OP_A1>(s, bufA.p, store(c) + size_t(t0) * P * 5 * NR, npair, t0, miT, tb, 1);
+            zconv<OP_A1>(s, bufA.p, store(c) + size_t(t0) * Q1 * 5 * NR, npair, t0, miQ, tb, 1);
           });
         }
     }
@@ -1554,8 +1570,10 @@ struct EngineT : Engine {
     }
     if (need_occ) {
       for (int c = 0; c < ns; ++c)
-        for (int a0 = 0; a0 < PI; a0 += T) {
-          const int nt = std::min(T, PI - a0);
+        for (int a0 = 0, nt = 0; a0 < PI; a0 += nt) {
+          // rows below Q1 read the store (a batch never straddles Q1); the others form their own pairs
+          const bool stored = keepA && a0 < Q1;
+          nt = std::min(T, (stored ? Q1 : PI) - a0);
           const long npair = long(nt) * P;
           const FusedArgs fa{P, nt, a0, S, chunk};
           if (bitc) {
@@ -1565,12 +1583,12 @@ struct EngineT : Engine {
             const cx<R>* b21 = bufB.p;
             const cx<R>* b12 = bufB.p + 4 * npair * NR;
             long sT21 = -1, sQ21 = 4, sT12 = -1, sQ12 = 4;
-            if (keepA) {
+            if (stored) {   // Q1 = P in the biorthogonal mode
               b21 = store(c) + (size_t(a0) * 5 + 1) * NR;
-              b12 = store(c) + (size_t(a0) * 5 * P + 1) * NR;
+              b12 = store(c) + (size_t(a0) * 5 * Q1 + 1) * NR;
               sT21 = 5;
-              sQ21 = 5L * P;
-              sT12 = 5L * P;
+              sQ21 = 5L * Q1;
+              sT12 = 5L * Q1;
               sQ12 = 5;
             } else {
               cx<R>* in12 = bufA.p + npair * NR;
@@ -1604,13 +1622,13 @@ struct EngineT : Engine {
                                    h5cpart.p + size_t(S) * nt * NR, H5CA[c]);
             });
           } else {
-            // row a = a0 + t, partner b = q; with the store: fields 1..4 of its pair b P + a
+            // row a = a0 + t, partner b = q; from the store: fields 1..4 of its pair b Q1 + a
             const cx<R>* b4 = bufB.p;
             long sT = -1, sQ = 4;
-            if (keepA) {
+            if (stored) {
               b4 = store(c) + (size_t(a0) * 5 + 1) * NR;
               sT = 5;
-              sQ = 5L * P;
+              sQ = 5L * Q1;
             } else {
               K(TC_K_XY_PAIR_OCC, fb * (npair + nt + P), [&] {
                 hipLaunchKernelGGL((k_pair_xy<R, N, true>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s,
@@ -1740,33 +1758,39 @@ struct EngineT : Engine {
         const double part = fb * nt * S;   // one working-precision field per (chunk, target)
         if (need_A) {
           const FusedArgs fa{P, nt, t0, S, chunk};
-          const cx<R>* zA = keepA ? store(c) + size_t(t0) * P * 5 * NR : bufB.p;
-          if (!keepA) {
-            K(TC_K_XY_PAIR_TGT, fb * (npair + nt + P), [&] {
-              hipLaunchKernelGGL((k_pair_xy<R, N, false>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, XS[c], tP, fa,
-                                 bufA.p);
+          if (Q1 < P) {   // the pairs of the partners q >= Q1 that the store does not hold: bufB [t][P - Q1][5]
+            const int PR = P - Q1;
+            const FusedArgs fr{PR, nt, t0, S, (PR + S - 1) / S};
+            MeshInfo miR = miT;
+            miR.P = PR;
+            miR.qoff = Q1;
+            const long nprR = long(nt) * PR;
+            K(TC_K_XY_PAIR_TGT, fb * (nprR + nt + PR), [&] {
+              hipLaunchKernelGGL((k_pair_xy<R, N, false>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s,
+                                 XS[c] + size_t(Q1) * NR, tP, fr, bufA.p);
             });
-            K(TC_K_ZCONV_A1, fb * 6.0 * npair + tabB, [&] {
-              zconv<OP_A1>(s, npair, t0, miT, tb, 1);
+            K(TC_K_ZCONV_A1, fb * 6.0 * nprR + tabB, [&] {
+              zconv<OP_A1>(s, nprR, t0, miR, tb, 1);
             });
           }
+          const cx<R>* stp = keepA ? store(c) : nullptr;
           // POL: the antiparallel 3b6 sources take the other channel's density; CN: complex densities
           const cx<R>* nA = pol ? NJ[o] : nullptr;
           const int do3b6 = int(m.m3b6 != 0);
           K(TC_K_FUSED_A, fb * ((m.m3b6 ? 9.0 : 5.0) * npair + 8.0 * P + nt) + 6.0 * part, [&] {
             const dim3 g(unsigned(nt) * N * S), b(NTH);
             if (pol && bitc)
-              hipLaunchKernelGGL((k_fused_A<R, N, true, true>), g, b, 0, s, zA, PSI[c], DL[c], HL[c], NJ[c], W[c], fa,
-                                 m, do3b6, miT, bm, mm, dfr.p, bufA.p, gpart.p, h4part.p, nA);
+              hipLaunchKernelGGL((k_fused_A<R, N, true, true>), g, b, 0, s, bufB.p, PSI[c], DL[c], HL[c], NJ[c], W[c], fa,
+                                 m, do3b6, miT, bm, mm, dfr.p, bufA.p, gpart.p, h4part.p, nA, stp, Q1);
             else if (pol)
-              hipLaunchKernelGGL((k_fused_A<R, N, true, false>), g, b, 0, s, zA, PSI[c], DL[c], HL[c], NJ[c], W[c], fa,
-                                 m, do3b6, miT, bm, mm, dfr.p, bufA.p, gpart.p, h4part.p, nA);
+              hipLaunchKernelGGL((k_fused_A<R, N, true, false>), g, b, 0, s, bufB.p, PSI[c], DL[c], HL[c], NJ[c], W[c], fa,
+                                 m, do3b6, miT, bm, mm, dfr.p, bufA.p, gpart.p, h4part.p, nA, stp, Q1);
             else if (bitc)
-              hipLaunchKernelGGL((k_fused_A<R, N, false, true>), g, b, 0, s, zA, PSI[c], DL[c], HL[c], NJ[c], W[c], fa,
-                                 m, do3b6, miT, bm, mm, dfr.p, bufA.p, gpart.p, h4part.p, nA);
+              hipLaunchKernelGGL((k_fused_A<R, N, false, true>), g, b, 0, s, bufB.p, PSI[c], DL[c], HL[c], NJ[c], W[c], fa,
+                                 m, do3b6, miT, bm, mm, dfr.p, bufA.p, gpart.p, h4part.p, nA, stp, Q1);
             else
-              hipLaunchKernelGGL((k_fused_A<R, N, false, false>), g, b, 0, s, zA, PSI[c], DL[c], HL[c], NJ[c], W[c],
-                                 fa, m, do3b6, miT, bm, mm, dfr.p, bufA.p, gpart.p, h4part.p, nA);
+              hipLaunchKernelGGL((k_fused_A<R, N, false, false>), g, b, 0, s, bufB.p, PSI[c], DL[c], HL[c], NJ[c], W[c],
+                                 fa, m, do3b6, miT, bm, mm, dfr.p, bufA.p, gpart.p, h4part.p, nA, stp, Q1);
           });
           K(TC_K_SUM_PARTS, 6.0 * part + 6.0 * fd * nt + 3.0 * fb * nt, [&] {
             hipLaunchKernelGGL((k_sum_parts<R, N>), dim3(nblk(long(nt) * NR)), dim3(256), 0, s, 1, S, nt, t0, 0,

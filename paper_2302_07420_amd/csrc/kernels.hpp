@@ -28,6 +28,7 @@ struct MeshInfo {
   int nbt;          // vectors per k-point of the target set (nb when the targets are the orbitals)
   const int* tk = nullptr;   // k-point of target block j / nbt (device; null: the block index itself)
   int nkb = 0;               // band k-points, coded nk .. nk + nkb - 1 in tk
+  int qoff = 0;              // partner q of a pass is orbital q + qoff (a pass over partners qoff .. P - 1)
 };
 
 __device__ __forceinline__ int kindex_delta(const MeshInfo& mi, int kto, int kfrom) {
@@ -344,7 +345,7 @@ struct FusedArgs {
 // index of the pair's shift in the kernel tables: k_jt - k_q (sign 1, target passes) or k_q - k_jt (sign 0);
 // target jt sits at k-point jt / nbt, partner q at q / nb
 __device__ __forceinline__ int pair_dindex(const MeshInfo& mi, int jt, int q, int sign) {
-  const int kt = mi.tk ? mi.tk[jt / mi.nbt] : jt / mi.nbt, kq = q / mi.nb;
+  const int kt = mi.tk ? mi.tk[jt / mi.nbt] : jt / mi.nbt, kq = (q + mi.qoff) / mi.nb;
   const int nkm = mi.n1 * mi.n2 * mi.n3;
   if (kt >= nkm) {   // band k-point: its own tables after the mesh differences, Delta = k_b - k_q then k_q - k_b
     const int nd = (2 * mi.n1 - 1) * (2 * mi.n2 - 1) * (2 * mi.n3 - 1);
@@ -1289,7 +1290,7 @@ template <typename R, int N, bool POL = false, bool CN = true>
 __global__ void __launch_bounds__((Fz<R, N>::NTH)) __attribute__((amdgpu_waves_per_eu(kFusedAWaves<R, N>)))
 k_fused_A(const cx<R>* buf5, const cx<R>* psi, const cx<R>* Dl, const cx<R>* Hl, const cx<R>* n, const double* w,
           FusedArgs fa, Masks m, int do3b6, MeshInfo mi, Basis<R> B, Basis<R> M, const double* dfr, cx<R>* src4,
-          cx<R>* gpart, cx<R>* h4part, const cx<R>* nA = nullptr) {
+          cx<R>* gpart, cx<R>* h4part, const cx<R>* nA = nullptr, const cx<R>* store = nullptr, int Q1 = 0) {
   using F = Fz<R, N>;
   constexpr int KP = F::KP, RB = F::RB, PL = F::PLANE;
   constexpr bool SPLIT = PassA<R, N>::SPLIT;
@@ -1314,8 +1315,14 @@ k_fused_A(const cx<R>* buf5, const cx<R>* psi, const cx<R>* Dl, const cx<R>* Hl,
   const R a0 = R(-m.m2ax), a1 = R((m.m2bx1 != 0 || m.m2bx2 != 0) ? -1 : 0), a2 = R(-m.m3a4);
   // the next partner's five pair planes are loaded into registers while this partner is transformed
   cx<R> pre[5][KP];
+  // the five pass-A planes of pair (t, q): partners q < Q1 from the resident store ([target][Q1][5]), the
+  // others from the batch's own z stage ([t][P - Q1][5])
+  auto pairsrc = [&](int q) -> const cx<R>* {
+    return q < Q1 ? store + (long(fa.t0 + wg.t) * Q1 + q) * 5 * NR
+                  : buf5 + (long(wg.t) * (fa.P - Q1) + (q - Q1)) * 5 * NR;
+  };
   auto fetch = [&](int q) {
-    const gptr<cx<R>> src = uniform_global(buf5 + (long(wg.t) * fa.P + q) * 5 * NR);
+    const gptr<cx<R>> src = uniform_global(pairsrc(q));
 #pragma unroll
     for (int f = 0; f < 5; ++f)
 #pragma unroll
@@ -1327,7 +1334,7 @@ k_fused_A(const cx<R>* buf5, const cx<R>* psi, const cx<R>* Dl, const cx<R>* Hl,
     const long pair = long(wg.t) * fa.P + q;
     const double* del = dfr + 3 * pair_dindex(mi, jt, q, 1);
     const R k1 = R(double(mfreq<N>(wg.x)) + del[0]);
-    const cx<R>* src = buf5 + pair * 5 * NR;
+    const cx<R>* src = pairsrc(q);
     const gptr<cx<R>> pq = uniform_global(psi + long(q) * NR);
     const gptr<cx<R>> dq = uniform_global(Dl + long(q) * NR);       // component d at dq + d P N^3
     const gptr<cx<R>> hq = uniform_global(Hl + long(q) * 3 * NR);   // component d at hq + d N^3
@@ -1335,24 +1342,33 @@ k_fused_A(const cx<R>* buf5, const cx<R>* psi, const cx<R>* Dl, const cx<R>* Hl,
     for (int g = 0; g < (SPLIT ? 2 : 1); ++g) {
       const bool par = !SPLIT || g == 0, anti = !SPLIT || g == 1;
       const int ab = SPLIT ? 0 : 4;   // LDS slot of Y_anti,1
+      // unsplit: the five planes are all requested before the first is used (left to itself the
+      // compiler waits for each load in turn); split: each field is loaded where it is stored
+      constexpr bool STAGE = !PF && !SPLIT;
+      if constexpr (STAGE) fetch(q);
+      auto field = [&](int f, int i) -> cx<R> {
+        if constexpr (PF || STAGE)
+          return pre[f][i];
+        else
+          return src[f * NR + wg.zo + RB * N * i];
+      };
       // load: slot 0 XV, slots 1-3 Y_par, slots ab..ab+2 Y_anti
 #pragma unroll
       for (int i = 0; i < KP; ++i) {
         const int so = wg.so0 + RB * F::LD * i;
-        const unsigned o = wg.zo + RB * N * i;
         const R k2 = R(double(mfreq<N>(wg.y0 + RB * i)) + del[1]);
         if (par) {
-          sm[so] = !PF ? src[o] : pre[0][i];
-          const cx<R> w0 = !PF ? src[NR + o] : pre[1][i];
+          sm[so] = field(0, i);
+          const cx<R> w0 = field(1, i);
           sm[PL + so] = mul_i(k1 * w0);
           sm[2 * PL + so] = mul_i(k2 * w0);
-          sm[3 * PL + so] = !PF ? src[2 * NR + o] : pre[2][i];
+          sm[3 * PL + so] = field(2, i);
         }
         if (anti) {
-          const cx<R> w0 = !PF ? src[3 * NR + o] : pre[3][i];
+          const cx<R> w0 = field(3, i);
           sm[ab * PL + so] = mul_i(k1 * w0);
           sm[(ab + 1) * PL + so] = mul_i(k2 * w0);
-          sm[(ab + 2) * PL + so] = !PF ? src[4 * NR + o] : pre[4][i];
+          sm[(ab + 2) * PL + so] = field(4, i);
         }
       }
       if (PF && q + 1 < wg.qe) fetch(q + 1);

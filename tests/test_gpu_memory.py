@@ -82,3 +82,53 @@ def test_allocator_argument_errors():
         op._check(op._L.tc_set_allocator(op._h, tc.ALLOC_FN(lambda n, u: None), tc.FREE_FN(), None),
                   "tc_set_allocator")
     op.close()
+
+
+def relerr(a, b):
+    scale = max(np.abs(x).max() for x in b)
+    return max(np.abs(x - y).max() for x, y in zip(a, b)) / scale
+
+
+def _store_budget(w, q1, elem_bytes, bitc=False):
+    """Caller budget at which the resident store holds q1 partner columns of every target: a batch of 8
+    targets of pair buffers plus q1 columns of 5 fields (one spin channel)."""
+    P, NR = w.nk * w.nband, int(np.prod(w.grid))
+    per_target = P * ((8 if bitc else 5) + 4) * NR * elem_bytes
+    return per_target * min(8, P) + q1 * 5 * P * NR * elem_bytes
+
+
+@pytest.mark.parametrize("prec,elem", [("fp64", 16), ("fp32", 8)])
+def test_partial_pair_store_equals_no_store(prec, elem):
+    """A caller budget between an eighth and all of the store: the store keeps the first Q1 partner columns;
+    the occupied pass reads them for its rows below Q1 and forms its own pairs for the others, and pass A
+    forms the pairs of the other partners.  Same operator, energy and orbital energies as without the store
+    (to rounding), and as the oracle; the occupied pass's own pair densities run for some rows only."""
+    from oracle.fftroute import ALL_TERMS, MULT, Problem
+
+    w = T.tiny_fcc(kmesh=(2, 2, 1), grid=12, ecut=2.0, nb=2, a=6.0, occ=[1.0, 0.8])
+    P = w.nk * w.nband
+    pr = Problem(w)
+    ref = [c.numpy() for c in pr.to_coeff(sum(MULT.get(t, 1) * pr.term(t, 0) for t in ALL_TERMS))]
+    p = tc.TC_PREC_FP64 if prec == "fp64" else tc.TC_PREC_FP32
+    tol = 1e-10 if prec == "fp64" else 2e-6
+    res = {}
+    # batches of 2 targets: without the store the occupied pass forms pairs for rows 0-1, 2-3, 4-5, 6-7; with
+    # 3 stored columns it reads rows 0-1 and 2 and forms pairs for 3-4, 5-6 and 7
+    for name, kw in (("none", dict(pair_store=False)), ("partial", dict(mem_budget=_store_budget(w, 3, elem))),
+                     ("full", dict())):
+        kw["batch"] = 2
+        _say(f"[gpu] partial pair store {prec}: {name}")
+        op = tc.from_workload(w, precision=p, **kw)
+        op.set_profiling(True)
+        op.kernel_stats(reset=True)
+        out = op.apply()
+        st = op.kernel_stats()
+        res[name] = (out, op.energy()[0], op.orbital_energies(), st["k_pair_xy<R,N,true>"]["launches"])
+        op.close()
+    occ = {k: v[3] for k, v in res.items()}
+    _say(f"    occupied-pass pair launches: {occ}")
+    assert occ == {"none": 4, "partial": 3, "full": 0}
+    for name in ("partial", "full"):
+        assert relerr(res[name][0], res["none"][0]) < (1e-12 if prec == "fp64" else 1e-6), name
+        assert abs(res[name][1] - res["none"][1]) < (1e-12 if prec == "fp64" else 1e-7) * abs(res["none"][1])
+    assert relerr(res["partial"][0], ref) < tol
