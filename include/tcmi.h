@@ -111,8 +111,9 @@ int tc_set_allocator(tc_ctx* ctx, void* (*alloc_fn)(size_t bytes, void* user),
 
 /* Bytes of device memory the resident pair store and the per-batch pair buffers (the two large
  * consumers) may take together; 0 (the default) sizes them from the device's memory.  With a budget the
- * store is kept when it and a batch of 8 targets fit, and the batches take what it leaves (at most
- * 32 GiB).  The next application resizes.  Results do not depend on it. */
+ * store takes the partner columns that fit beside a batch of 8 targets (tc_set_pair_store), and the
+ * batches take what it leaves (at most 32 GiB).  The next application resizes.  Results do not depend
+ * on it. */
 int tc_set_memory_budget(tc_ctx* ctx, size_t bytes);
 
 /* The hipStream_t the context enqueues its work on (the caller's, or the one it created). */
@@ -407,17 +408,20 @@ int tc_last_timing(tc_ctx* ctx, double* total_ms, double* stage_ms, int n);
  * device's memory (between 8 and 32 GiB) of pair buffers.  Results do not depend on it; tests use small values to cover batching. */
 int tc_set_batch(tc_ctx* ctx, int targets_per_batch);
 
-/* Resident pair store (on = 1, the default): when tc_apply_all* runs with the orbitals as targets
- * and every pair's pass-A z-stage output (5 P^2 fields of N1 N2 N3 working-precision complex values)
- * fits on the device with a quarter of its memory (at least 16 GiB) left free, those outputs are
- * computed once and kept, and the occupied-occupied pass reads its four fields per pair from them
- * (the pair (a, b) of that pass is the pass-A pair with target b and partner a: same density
+/* Resident pair store (on = 1, the default): when tc_apply_all* runs with the orbitals as targets,
+ * the pass-A z-stage outputs of the pairs (t, q) of every target t and of the first Q1 partners q
+ * (5 Q1 P fields of N1 N2 N3 working-precision complex values per spin channel) are computed once
+ * and kept, and the occupied-occupied pass reads its four fields per pair from them for its rows
+ * a < Q1 (the pair (a, b) of that pass is the pass-A pair with target b and partner a: same density
  * conj(chi_a) psi_b, same momentum k_b - k_a; in the biorthogonal mode its second convolution, of
  * conj(chi_b) psi_a at k_a - k_b, is the pass-A pair with target a and partner b) instead of
- * recomputing them.  Otherwise, and with on = 0, both passes transform their own pair densities.
- * Results do not depend on it; the store is released when it is switched off.  Trial vectors, band
- * k-points, symmetry-reduced and spin-polarised runs always use the batched form.  With a budget
- * (tc_set_memory_budget) the store is kept when it and 8 targets of pair buffers fit in it. */
+ * recomputing them; pass A then forms only the pairs of the partners q >= Q1.  Q1 = P when every
+ * pair fits; otherwise as many partner columns as fit with an eighth of the device's memory (at
+ * least 16 GiB) left free after the batch buffers, and none when fewer than P/8 fit (the
+ * biorthogonal mode stores every pair or none).  With a budget (tc_set_memory_budget) the store
+ * takes what is left of it after 8 targets of pair buffers.  With on = 0 both passes transform their
+ * own pair densities.  Results do not depend on it; the store is released when it is switched off.
+ * Trial vectors, band k-points and symmetry-reduced runs always use the batched form. */
 int tc_set_pair_store(tc_ctx* ctx, int on);
 
 /* Kernels timed by tc_kernel_stats (device time between HIP events recorded on the

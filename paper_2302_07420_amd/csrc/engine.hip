@@ -12,6 +12,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <complex>
 #include <cstdio>
@@ -315,6 +316,7 @@ struct DBuf {
       hipError_t e = hipMalloc(&p, count * sizeof(T));
       if (e != hipSuccess) {
         p = nullptr;
+        (void)hipGetLastError();   // the failure is reported here, not to the caller's next launch check
         throw TcError(TC_ERR_OOM, "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed");
       }
       al = nullptr;
@@ -1165,20 +1167,31 @@ struct EngineT : Engine {
     zconv<OP>(s, bufA.p, bufB.p, npair, t0, mi, tb, sign);
   }
 
-  void release_pair_store() override { allB.release(); }
+  void release_pair_store() override {
+    allB.release();
+    store_cap_ = INT_MAX;
+  }
 
   // Bytes of per-batch pair buffers (bufA, bufB) of one target, and of the smallest batch worth keeping
   // next to the resident store
   static size_t per_target_bytes(const Problem& pb) {
     return size_t(pb.P()) * ((pb.bitc ? 8 : 5) + 4) * NR * sizeof(cx<R>);
   }
+  // Bytes of bufA and bufB at a pair budget (the batch of ensure)
+  static size_t batch_bytes(const Problem& pb, size_t budget_bytes) {
+    const size_t per_t = per_target_bytes(pb), P = size_t(std::max(1, pb.P()));
+    size_t T = std::max<size_t>(1, std::min(P, budget_bytes / per_t));
+    if (pb.batch > 0) T = std::min(size_t(pb.batch), P);
+    return T * per_t;
+  }
 
   // The resident store of pass-A z-stage outputs: the pairs (t, q) of every target t and of the first Q1
   // partners q, [t][Q1][5] fields per spin channel.  Q1 = P when every pair fits; fewer partner columns when
   // only part of them does (TC mode: the occupied pass reads the store for its rows a < Q1 and forms its
   // own pairs for the others; the biorthogonal occupied pass needs the pairs of both orders, so there the
-  // store holds every pair or none).  Without a caller budget it may take what leaves a quarter of the
-  // device (at least 16 GiB) free, the store it already holds counted as free; with a budget
+  // store holds every pair or none).  Without a caller budget it may take what leaves an eighth of the
+  // device (at least 16 GiB) free once the batch buffers that follow it are allocated, the store it
+  // already holds counted as free, and it keeps using every column it holds; with a budget
   // (tc_set_memory_budget), what leaves a batch of 8 targets of pair buffers.  Fewer than an eighth of the
   // columns are not worth the split passes: no store then.  Never under the no-allocation scratch.
   // Returns Q1 (0: no store).
@@ -1190,6 +1203,10 @@ struct EngineT : Engine {
       return 0;
     };
     if (!pb.pair_store || P == 0) return none();
+    if (P != cap_P_) {   // the cap counts columns of one problem size
+      store_cap_ = INT_MAX;
+      cap_P_ = P;
+    }
     const size_t col = size_t(5) * pb.nspin * P * NR * sizeof(cx<R>);   // bytes of one partner column
     size_t avail = 0;
     if (pb.mem_budget) {
@@ -1199,22 +1216,33 @@ struct EngineT : Engine {
       size_t fr = 0, tot = 0;
       if (hipMemGetInfo(&fr, &tot) != hipSuccess) return none();
       const size_t have = allB.p ? allB.n * sizeof(cx<R>) : 0;
-      const size_t reserve = std::max<size_t>(tot / 4, size_t(16) << 30);
+      // the batch buffers are sized after the store: what they still have to take counts as taken
+      const size_t held = ((bufA.p ? bufA.n : 0) + (bufB.p ? bufB.n : 0)) * sizeof(cx<R>);
+      const size_t want = batch_bytes(pb, pair_budget(pb));
+      const size_t reserve = std::max<size_t>(tot / 8, size_t(16) << 30) + (want > held ? want - held : 0);
       avail = fr + have > reserve ? fr + have - reserve : 0;
     }
     int q1 = int(std::min<size_t>(size_t(P), avail / col));
+    if (!pb.mem_budget && allB.p) q1 = std::max(q1, int(std::min<size_t>(size_t(P), allB.n * sizeof(cx<R>) / col)));
+    q1 = std::min(q1, store_cap_);   // a size that failed is not asked for again
     if (pb.bitc && q1 < P) q1 = 0;
     if (q1 < (P + 7) / 8) return none();
-    const size_t need = col / sizeof(cx<R>) * q1;
-    if (allB.n >= need) return q1;
+    const size_t per_col = col / sizeof(cx<R>);
+    if (allB.n >= per_col * q1) return q1;
     allB.release();
-    try {
-      allB.alloc(need);
-    } catch (const TcError&) {
-      return 0;
+    // on failure: fewer columns, down to the fewest worth keeping
+    for (; q1 >= (P + 7) / 8 && (!pb.bitc || q1 == P); q1 -= std::max(1, P / 16)) {
+      try {
+        allB.alloc(per_col * q1);
+        return q1;
+      } catch (const TcError&) {
+        store_cap_ = q1 - 1;
+      }
     }
-    return q1;
+    return 0;
   }
+  int store_cap_ = INT_MAX;   // most partner columns an allocation may still ask for (at P = cap_P_)
+  int cap_P_ = -1;
 
   // Bytes of per-batch pair buffers.  Without a caller budget: an eighth of the device's memory, between
   // 8 and 32 GiB (32 GiB on a 288 GB device: 134 targets per batch at 256 orbitals and 24^3 in FP32);

@@ -132,3 +132,60 @@ def test_partial_pair_store_equals_no_store(prec, elem):
         assert relerr(res[name][0], res["none"][0]) < (1e-12 if prec == "fp64" else 1e-6), name
         assert abs(res[name][1] - res["none"][1]) < (1e-12 if prec == "fp64" else 1e-7) * abs(res["none"][1])
     assert relerr(res["partial"][0], ref) < tol
+
+
+def test_store_takes_fewer_columns_when_an_allocation_fails():
+    """An allocator that refuses every request above 12 MB: the whole store (20 MB in FP64) is refused, and
+    the store settles on the most partner columns that it grants (7 of 12); the next application asks for
+    no refused size again.  The operator equals the one without the store."""
+    import torch
+
+    w = _case()
+    P = w.nk * w.nband
+    _say("[gpu] pair store under an allocator that refuses requests above 12 MB")
+    ref = tc.from_workload(w, precision=tc.TC_PREC_FP64, pair_store=False, batch=4)
+    ref.set_profiling(True)
+    ref.kernel_stats(reset=True)
+    hc_ref = ref.apply()
+    own_ref = ref.kernel_stats()["k_pair_xy<R,N,true>"]["launches"]
+    ref.close()
+    cap, refused = 12 << 20, []
+    op = tc.TCOperator(0)
+    stream = op.stream()
+
+    def _alloc(nbytes, user):
+        if nbytes > cap:
+            refused.append(int(nbytes))
+            return None
+        return torch.cuda.caching_allocator_alloc(int(nbytes), 0, stream)
+
+    def _free(ptr, nbytes, user):
+        torch.cuda.caching_allocator_delete(ptr)
+
+    cbs = (tc.ALLOC_FN(_alloc), tc.FREE_FN(_free))
+    op._check(op._L.tc_set_allocator(op._h, cbs[0], cbs[1], None), "tc_set_allocator")
+    op.set_memory_budget(64 << 20)
+    op.set_batch(4)
+    op.set_cell(w.lattice)
+    op.set_kmesh(*w.kmesh)
+    op.set_grid(*w.grid)
+    for ik, m in enumerate(w.miller):
+        op.set_basis(ik, m)
+    op.set_jastrow(w.A, w.C)
+    op.set_options(tc.TC_PREC_FP64, w.alpha, True, tc.TERM_ALL)
+    for ik in range(w.nk):
+        op.load_orbitals(ik, w.right[ik], w.occ[ik])
+    op.set_profiling(True)
+    outs = []
+    for _ in range(2):
+        op.kernel_stats(reset=True)
+        outs.append((op.apply(), op.kernel_stats()["k_pair_xy<R,N,true>"]["launches"], len(refused)))
+    op.close()
+    col = 5 * P * int(np.prod(w.grid)) * 16
+    _say(f"    refused {[r // col for r in refused]} columns; own occupied-pass pair launches "
+         f"{[o[1] for o in outs]} (without the store {own_ref})")
+    assert refused and all(r > cap for r in refused) and P * col in refused
+    assert outs[1][2] == outs[0][2]                         # no refused size asked for again
+    assert own_ref == 3 and outs[0][1] == outs[1][1] == 2   # rows 7-10 and 11 form their own pairs
+    for hc, _, _ in outs:
+        assert relerr(hc, hc_ref) < 1e-12
