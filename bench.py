@@ -242,6 +242,8 @@ def main():
     E32 = e32[-1][0]
     tot, stages = op32.timing()
     log(f"fp32: {ms32:.2f} ms/step (wall {wall32:.2f}), E = {E32:.12f}")
+    op32.close()   # its resident store holds most of the device
+    del keep32
 
     split = None
     if not args.no_split:
@@ -443,7 +445,6 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(res), flush=True)
-    op32.close()
 
 
 if __name__ == "__main__":

@@ -405,7 +405,9 @@ int tc_last_timing(tc_ctx* ctx, double* total_ms, double* stage_ms, int n);
 
 /* Number of target orbitals processed per pass-A/B batch (and occupied partners per
  * batch of the occupied-occupied pass).  0 (default) sizes batches to an eighth of the
- * device's memory (between 8 and 32 GiB) of pair buffers.  Results do not depend on it; tests use small values to cover batching. */
+ * device's memory (between 8 and 32 GiB) of pair buffers.  Where the device cannot hold a batch's
+ * pair buffers, the batch halves until it fits (down to one target).  Results do not depend on it;
+ * tests use small values to cover batching. */
 int tc_set_batch(tc_ctx* ctx, int targets_per_batch);
 
 /* Resident pair store (on = 1, the default): when tc_apply_all* runs with the orbitals as targets,

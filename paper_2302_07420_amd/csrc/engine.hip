@@ -1289,8 +1289,20 @@ struct EngineT : Engine {
     const size_t per_t = per_target_bytes(pb);
     T = int(std::max<size_t>(1, std::min<size_t>(size_t(P), budget_bytes / per_t)));
     if (pb.batch > 0) T = std::min(pb.batch, P);
-    bufA.alloc(size_t(T) * P * 4 * NR);
-    bufB.alloc(size_t(T) * P * nB * NR);
+    for (;;) {
+      try {
+        bufA.alloc(size_t(T) * P * 4 * NR);
+        bufB.alloc(size_t(T) * P * nB * NR);
+        break;
+      } catch (const TcError& e) {
+        // the device is fuller than its free memory said (another context, the caller's tensors): fewer
+        // targets per batch, which changes no result
+        if (t_arena || T == 1 || e.code != TC_ERR_OOM) throw;
+        bufA.release();
+        bufB.release();
+        T = (T + 1) / 2;
+      }
+    }
     h4.alloc(size_t(3) * T * NR);
     Z.alloc(size_t(3) * T * NR);
     g.alloc(size_t(T) * NR);

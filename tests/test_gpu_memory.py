@@ -134,22 +134,11 @@ def test_partial_pair_store_equals_no_store(prec, elem):
     assert relerr(res["partial"][0], ref) < tol
 
 
-def test_store_takes_fewer_columns_when_an_allocation_fails():
-    """An allocator that refuses every request above 12 MB: the whole store (20 MB in FP64) is refused, and
-    the store settles on the most partner columns that it grants (7 of 12); the next application asks for
-    no refused size again.  The operator equals the one without the store."""
+def _refusing_op(w, cap, refused, budget=0, batch=0, pair_store=True):
+    """An FP64 operator of w whose device memory comes from PyTorch's caching allocator through callbacks
+    that refuse (return NULL for) every request above cap bytes, recording the refused sizes."""
     import torch
 
-    w = _case()
-    P = w.nk * w.nband
-    _say("[gpu] pair store under an allocator that refuses requests above 12 MB")
-    ref = tc.from_workload(w, precision=tc.TC_PREC_FP64, pair_store=False, batch=4)
-    ref.set_profiling(True)
-    ref.kernel_stats(reset=True)
-    hc_ref = ref.apply()
-    own_ref = ref.kernel_stats()["k_pair_xy<R,N,true>"]["launches"]
-    ref.close()
-    cap, refused = 12 << 20, []
     op = tc.TCOperator(0)
     stream = op.stream()
 
@@ -164,8 +153,13 @@ def test_store_takes_fewer_columns_when_an_allocation_fails():
 
     cbs = (tc.ALLOC_FN(_alloc), tc.FREE_FN(_free))
     op._check(op._L.tc_set_allocator(op._h, cbs[0], cbs[1], None), "tc_set_allocator")
-    op.set_memory_budget(64 << 20)
-    op.set_batch(4)
+    op._refusing_cbs = cbs
+    if budget:
+        op.set_memory_budget(budget)
+    if batch:
+        op.set_batch(batch)
+    if not pair_store:
+        op.set_pair_store(False)
     op.set_cell(w.lattice)
     op.set_kmesh(*w.kmesh)
     op.set_grid(*w.grid)
@@ -175,6 +169,24 @@ def test_store_takes_fewer_columns_when_an_allocation_fails():
     op.set_options(tc.TC_PREC_FP64, w.alpha, True, tc.TERM_ALL)
     for ik in range(w.nk):
         op.load_orbitals(ik, w.right[ik], w.occ[ik])
+    return op
+
+
+def test_store_takes_fewer_columns_when_an_allocation_fails():
+    """An allocator that refuses every request above 12 MB: the whole store (20 MB in FP64) is refused, and
+    the store settles on the most partner columns that it grants (7 of 12); the next application asks for
+    no refused size again.  The operator equals the one without the store."""
+    w = _case()
+    P = w.nk * w.nband
+    _say("[gpu] pair store under an allocator that refuses requests above 12 MB")
+    ref = tc.from_workload(w, precision=tc.TC_PREC_FP64, pair_store=False, batch=4)
+    ref.set_profiling(True)
+    ref.kernel_stats(reset=True)
+    hc_ref = ref.apply()
+    own_ref = ref.kernel_stats()["k_pair_xy<R,N,true>"]["launches"]
+    ref.close()
+    cap, refused = 12 << 20, []
+    op = _refusing_op(w, cap, refused, budget=64 << 20, batch=4)
     op.set_profiling(True)
     outs = []
     for _ in range(2):
@@ -189,3 +201,24 @@ def test_store_takes_fewer_columns_when_an_allocation_fails():
     assert own_ref == 3 and outs[0][1] == outs[1][1] == 2   # rows 7-10 and 11 form their own pairs
     for hc, _, _ in outs:
         assert relerr(hc, hc_ref) < 1e-12
+
+
+def test_batch_shrinks_when_its_buffers_are_refused():
+    """Without a budget the 12 targets of the case make one batch (bufA 16 MB, bufB 20 MB in FP64); under
+    an allocator that refuses requests above 12 MB the batch halves to 6 targets, and the operator equals
+    the unrestricted one."""
+    w = _case()
+    _say("[gpu] batch buffers under an allocator that refuses requests above 12 MB")
+    ref = tc.from_workload(w, precision=tc.TC_PREC_FP64, pair_store=False)
+    hc_ref = ref.apply()
+    E_ref = ref.energy()[0]
+    ref.close()
+    refused = []
+    op = _refusing_op(w, 12 << 20, refused, pair_store=False)
+    hc = op.apply()
+    E = op.energy()[0]
+    op.close()
+    _say(f"    refused {refused} bytes")
+    assert refused
+    assert relerr(hc, hc_ref) < 1e-12
+    assert abs(E - E_ref) < 1e-12 * abs(E_ref)
