@@ -1185,11 +1185,12 @@ struct EngineT : Engine {
     return T * per_t;
   }
 
-  // The resident store of pass-A z-stage outputs: the pairs (t, q) of every target t and of the first Q1
-  // partners q, [t][Q1][5] fields per spin channel.  Q1 = P when every pair fits; fewer partner columns when
-  // only part of them does (TC mode: the occupied pass reads the store for its rows a < Q1 and forms its
-  // own pairs for the others; the biorthogonal occupied pass needs the pairs of both orders, so there the
-  // store holds every pair or none).  Without a caller budget it may take what leaves an eighth of the
+  // The resident store of pass-A z-stage outputs, [pair][5] fields per spin channel, of the first Q1 partner
+  // columns.  TC mode: triangular rows, the pairs (t, q) with q <= t and q < Q1 (tri_row; the pair (t, q) of
+  // q > t is the reflected conjugate of (q, t)), so every pair with min(t, q) < Q1 is available; the
+  // occupied pass reads it for its rows a < Q1 and forms its own pairs for the others, and pass A forms the
+  // pairs of the targets and partners at or above Q1.  Biorthogonal mode: [t][P][5], every pair (the two
+  // orders of a pair are not conjugate there) or none.  Q1 = P when every pair fits.  Without a caller budget it may take what leaves an eighth of the
   // device (at least 16 GiB) free once the batch buffers that follow it are allocated, the store it
   // already holds counted as free, and it keeps using every column it holds; with a budget
   // (tc_set_memory_budget), what leaves a batch of 8 targets of pair buffers.  Fewer than an eighth of the
@@ -1207,7 +1208,14 @@ struct EngineT : Engine {
       store_cap_ = INT_MAX;
       cap_P_ = P;
     }
-    const size_t col = size_t(5) * pb.nspin * P * NR * sizeof(cx<R>);   // bytes of one partner column
+    // elements of the store with Q1 partner columns: triangular rows in TC mode, P x Q1 in the biorthogonal one
+    const size_t per_pair = size_t(5) * pb.nspin * NR;
+    auto elems = [&](int q1) { return per_pair * (pb.bitc ? size_t(P) * q1 : size_t(tri_row(P, q1))); };
+    auto fit = [&](size_t bytes) {   // most columns within bytes
+      int q = 0;
+      while (q < P && elems(q + 1) * sizeof(cx<R>) <= bytes) ++q;
+      return q;
+    };
     size_t avail = 0;
     if (pb.mem_budget) {
       const size_t keep = per_target_bytes(pb) * std::min(8, P);
@@ -1222,18 +1230,17 @@ struct EngineT : Engine {
       const size_t reserve = std::max<size_t>(tot / 8, size_t(16) << 30) + (want > held ? want - held : 0);
       avail = fr + have > reserve ? fr + have - reserve : 0;
     }
-    int q1 = int(std::min<size_t>(size_t(P), avail / col));
-    if (!pb.mem_budget && allB.p) q1 = std::max(q1, int(std::min<size_t>(size_t(P), allB.n * sizeof(cx<R>) / col)));
+    int q1 = fit(avail);
+    if (!pb.mem_budget && allB.p) q1 = std::max(q1, fit(allB.n * sizeof(cx<R>)));
     q1 = std::min(q1, store_cap_);   // a size that failed is not asked for again
     if (pb.bitc && q1 < P) q1 = 0;
     if (q1 < (P + 7) / 8) return none();
-    const size_t per_col = col / sizeof(cx<R>);
-    if (allB.n >= per_col * q1) return q1;
+    if (allB.n >= elems(q1)) return q1;
     allB.release();
     // on failure: fewer columns, down to the fewest worth keeping
     for (; q1 >= (P + 7) / 8 && (!pb.bitc || q1 == P); q1 -= std::max(1, P / 16)) {
       try {
-        allB.alloc(per_col * q1);
+        allB.alloc(elems(q1));
         return q1;
       } catch (const TcError&) {
         store_cap_ = q1 - 1;
@@ -1395,6 +1402,7 @@ struct EngineT : Engine {
     // caller's budget.)
     const int Q1 = (!ts && !sym && need_occ && need_A) ? pair_store(pb) : 0;   // stored partner columns
     const bool keepA = Q1 > 0;
+    const bool tri = keepA && !pb.bitc;   // TC mode: the triangular store (tri_row)
     ensure(pb, pair_budget(pb));
     // targets: the orbitals, or nbt trial vectors per k-point
     const int nbt = ts ? ts->nvec : nb;
@@ -1436,8 +1444,10 @@ struct EngineT : Engine {
     const double* W[2] = {sh.w.p, sh.w.p + P};
     const size_t cofs = size_t(2) * P * pb.npw_max;   // doubles per channel of the coefficients
     const size_t tcofs = size_t(2) * NTG * tnpm;      // doubles per channel of the target coefficients
-    // the resident store of channel c: [P][Q1][5][N^3] pass-A z-stage outputs, pair-major in target order
-    auto store = [&](int c) { return allB.p + size_t(c) * P * Q1 * 5 * NR; };
+    // the resident store of channel c: pass-A z-stage outputs [pair][5][N^3], pair-major in target order;
+    // triangular rows in TC mode, [P][Q1] in the biorthogonal mode
+    const size_t spairs = tri ? size_t(tri_row(P, Q1)) : size_t(P) * Q1;
+    auto store = [&](int c) { return allB.p + size_t(c) * spairs * 5 * NR; };
     // algorithmic bytes: fields each launch must read or write once (working precision)
     const double fb = double(sizeof(cx<R>)) * NR;
     const double fd = double(sizeof(cx<double>)) * NR;
@@ -1579,7 +1589,32 @@ struct EngineT : Engine {
 
     // ---- 2: occupied-occupied pair pass (Algs. 3a2, 3a4 and 3b2/3b5 first loops), per channel
     const int chunk = (P + S - 1) / S;
-    if (keepA) {   // the pairs (t, q < Q1) of every target, before the occupied pass
+    if (tri) {   // the pairs (t, q <= t, q < Q1) of every target, before the occupied pass
+      for (int c = 0; c < ns; ++c)
+        for (int t0 = 0; t0 < P; t0 += T) {
+          const int nt = std::min(T, P - t0);
+          const int qn = std::min(t0 + nt, Q1);   // partners formed for the batch: bufA [t][qn]
+          const FusedArgs fa{qn, nt, t0, S, (qn + S - 1) / S};
+          K(TC_K_XY_PAIR_TGT, fb * (double(nt) * qn + nt + qn), [&] {
+            hipLaunchKernelGGL((k_pair_xy<R, N, false>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, XS[c], PSI[c],
+                               fa, bufA.p);
+          });
+          const long rows = tri_row(t0 + nt, Q1) - tri_row(t0, Q1);   // pairs the batch's rows hold
+          K(TC_K_ZCONV_A1, fb * 6.0 * rows + tabB, [&] {
+            if (t0 >= Q1) {   // Q1 pairs in every row
+              const MeshInfo miQ{pb.n1, pb.n2, pb.n3, nb, Q1, nb};
+              zconv<OP_A1>(s, bufA.p, store(c) + size_t(tri_row(t0, Q1)) * 5 * NR, long(nt) * Q1, t0, miQ, tb, 1);
+            } else {
+              for (int t = 0; t < nt; ++t) {   // row t0 + t: partners 0 .. min(t0 + t, Q1 - 1)
+                const int L = std::min(t0 + t + 1, Q1);
+                const MeshInfo miL{pb.n1, pb.n2, pb.n3, nb, L, nb};
+                zconv<OP_A1>(s, bufA.p + size_t(t) * qn * NR, store(c) + size_t(tri_row(t0 + t, Q1)) * 5 * NR, L,
+                             t0 + t, miL, tb, 1);
+              }
+            }
+          });
+        }
+    } else if (keepA) {   // the pairs (t, q < Q1) of every target, before the occupied pass
       const MeshInfo miQ{pb.n1, pb.n2, pb.n3, nb, Q1, nb};
       const int chunkQ = (Q1 + S - 1) / S;
       for (int c = 0; c < ns; ++c)
@@ -1662,14 +1697,12 @@ struct EngineT : Engine {
                                    h5cpart.p + size_t(S) * nt * NR, H5CA[c]);
             });
           } else {
-            // row a = a0 + t, partner b = q; from the store: fields 1..4 of its pair b Q1 + a
+            // row a = a0 + t, partner b = q; from the store: fields 1..4 of its pair (b, a), or of (a, b)
+            // reflected and conjugated (triangular store)
             const cx<R>* b4 = bufB.p;
+            const cx<R>* trs = stored ? store(c) : nullptr;
             long sT = -1, sQ = 4;
-            if (stored) {
-              b4 = store(c) + (size_t(a0) * 5 + 1) * NR;
-              sT = 5;
-              sQ = 5L * Q1;
-            } else {
+            if (!stored) {
               K(TC_K_XY_PAIR_OCC, fb * (npair + nt + P), [&] {
                 hipLaunchKernelGGL((k_pair_xy<R, N, true>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s,
                                    sym ? psiT.p : PSI[c], PSI[c], fa, bufA.p);
@@ -1681,10 +1714,10 @@ struct EngineT : Engine {
             K(TC_K_FUSED_O, fb * (4.0 * npair + P) + (pol ? 4.5 : 3.5) * fb * nt * S, [&] {
               if (pol)
                 hipLaunchKernelGGL((k_fused_O<R, N, true>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, b4, PSI[c],
-                                   W[c], fa, mi, rc, dfr.p, h5part.p, H3part.p, sT, sQ);
+                                   W[c], fa, mi, rc, dfr.p, h5part.p, H3part.p, sT, sQ, trs, Q1);
               else
                 hipLaunchKernelGGL((k_fused_O<R, N>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, b4, PSI[c], W[c],
-                                   fa, mi, rc, dfr.p, h5part.p, H3part.p, sT, sQ);
+                                   fa, mi, rc, dfr.p, h5part.p, H3part.p, sT, sQ, trs, Q1);
             });
             K(TC_K_SUM_PARTS, (pol ? 5.0 : 4.0) * fb * nt * (S + 1), [&] {
               hipLaunchKernelGGL((k_sum_parts<R, N>), dim3(nblk(long(nt) * NR)), dim3(256), 0, s, 0, S, nt, a0, 0,
@@ -1798,7 +1831,10 @@ struct EngineT : Engine {
         const double part = fb * nt * S;   // one working-precision field per (chunk, target)
         if (need_A) {
           const FusedArgs fa{P, nt, t0, S, chunk};
-          if (Q1 < P) {   // the pairs of the partners q >= Q1 that the store does not hold: bufB [t][P - Q1][5]
+          // the pairs of the partners q >= Q1 that the store does not hold: bufB [t][P - Q1][5] (the triangular
+          // store holds them, reflected, for targets below Q1)
+          const bool formA = Q1 < P && (!tri || t0 + nt > Q1);
+          if (formA) {
             const int PR = P - Q1;
             const FusedArgs fr{PR, nt, t0, S, (PR + S - 1) / S};
             MeshInfo miR = miT;
@@ -1821,16 +1857,16 @@ struct EngineT : Engine {
             const dim3 g(unsigned(nt) * N * S), b(NTH);
             if (pol && bitc)
               hipLaunchKernelGGL((k_fused_A<R, N, true, true>), g, b, 0, s, bufB.p, PSI[c], DL[c], HL[c], NJ[c], W[c], fa,
-                                 m, do3b6, miT, bm, mm, dfr.p, bufA.p, gpart.p, h4part.p, nA, stp, Q1);
+                                 m, do3b6, miT, bm, mm, dfr.p, bufA.p, gpart.p, h4part.p, nA, stp, Q1, int(tri), int(formA));
             else if (pol)
               hipLaunchKernelGGL((k_fused_A<R, N, true, false>), g, b, 0, s, bufB.p, PSI[c], DL[c], HL[c], NJ[c], W[c], fa,
-                                 m, do3b6, miT, bm, mm, dfr.p, bufA.p, gpart.p, h4part.p, nA, stp, Q1);
+                                 m, do3b6, miT, bm, mm, dfr.p, bufA.p, gpart.p, h4part.p, nA, stp, Q1, int(tri), int(formA));
             else if (bitc)
               hipLaunchKernelGGL((k_fused_A<R, N, false, true>), g, b, 0, s, bufB.p, PSI[c], DL[c], HL[c], NJ[c], W[c], fa,
-                                 m, do3b6, miT, bm, mm, dfr.p, bufA.p, gpart.p, h4part.p, nA, stp, Q1);
+                                 m, do3b6, miT, bm, mm, dfr.p, bufA.p, gpart.p, h4part.p, nA, stp, Q1, int(tri), int(formA));
             else
               hipLaunchKernelGGL((k_fused_A<R, N, false, false>), g, b, 0, s, bufB.p, PSI[c], DL[c], HL[c], NJ[c], W[c],
-                                 fa, m, do3b6, miT, bm, mm, dfr.p, bufA.p, gpart.p, h4part.p, nA, stp, Q1);
+                                 fa, m, do3b6, miT, bm, mm, dfr.p, bufA.p, gpart.p, h4part.p, nA, stp, Q1, int(tri), int(formA));
           });
           K(TC_K_SUM_PARTS, 6.0 * part + 6.0 * fd * nt + 3.0 * fb * nt, [&] {
             hipLaunchKernelGGL((k_sum_parts<R, N>), dim3(nblk(long(nt) * NR)), dim3(256), 0, s, 1, S, nt, t0, 0,

@@ -342,6 +342,15 @@ struct FusedArgs {
   int P, T, t0, S, chunk;     // orbitals, targets in batch, first target, partner chunks, partners per chunk
 };
 
+// The resident pair store of TC mode is triangular: row t holds the pass-A pairs (t, q) with q <= t and
+// q < Q1, min(t + 1, Q1) of them, rows one after another.  The pair (t, q) of q > t is read from the pair
+// (q, t): its density is the conjugate of (t, q)'s and its shift the negative, and every kernel that
+// multiplies it is real in real space and zero on the Nyquist planes, so its z-stage output is the
+// conjugate of (q, t)'s at the reflected xy frequencies (-Gx, -Gy).  Offset (in pairs) of row t:
+__host__ __device__ __forceinline__ long tri_row(int t, int Q1) {
+  return t < Q1 ? long(t) * (t + 1) / 2 : long(Q1) * (Q1 + 1) / 2 + long(t - Q1) * Q1;
+}
+
 // index of the pair's shift in the kernel tables: k_jt - k_q (sign 1, target passes) or k_q - k_jt (sign 0);
 // target jt sits at k-point jt / nbt, partner q at q / nb
 __device__ __forceinline__ int pair_dindex(const MeshInfo& mi, int jt, int q, int sign) {
@@ -649,6 +658,11 @@ struct PlaneWG {
       return sigma48(y0 + F::RB * i) * F::LD + sx;
     else
       return so(i);
+  }
+  // element offset within a volume of owned point i reflected through the xy origin, (-y, -x) mod N
+  __device__ __forceinline__ unsigned flip(int i) const {
+    const int y = y0 + F::RB * i;
+    return unsigned(z * N * N + (y == 0 ? 0 : N - y) * N + (x == 0 ? 0 : N - x));
   }
   // between a round's reads at ss() and the next round's writes at so(): a barrier where they differ
   __device__ __forceinline__ void end_round() const {
@@ -1290,7 +1304,8 @@ template <typename R, int N, bool POL = false, bool CN = true>
 __global__ void __launch_bounds__((Fz<R, N>::NTH)) __attribute__((amdgpu_waves_per_eu(kFusedAWaves<R, N>)))
 k_fused_A(const cx<R>* buf5, const cx<R>* psi, const cx<R>* Dl, const cx<R>* Hl, const cx<R>* n, const double* w,
           FusedArgs fa, Masks m, int do3b6, MeshInfo mi, Basis<R> B, Basis<R> M, const double* dfr, cx<R>* src4,
-          cx<R>* gpart, cx<R>* h4part, const cx<R>* nA = nullptr, const cx<R>* store = nullptr, int Q1 = 0) {
+          cx<R>* gpart, cx<R>* h4part, const cx<R>* nA = nullptr, const cx<R>* store = nullptr, int Q1 = 0,
+          int tri = 0, int formed = 1) {
   using F = Fz<R, N>;
   constexpr int KP = F::KP, RB = F::RB, PL = F::PLANE;
   constexpr bool SPLIT = PassA<R, N>::SPLIT;
@@ -1315,18 +1330,39 @@ k_fused_A(const cx<R>* buf5, const cx<R>* psi, const cx<R>* Dl, const cx<R>* Hl,
   const R a0 = R(-m.m2ax), a1 = R((m.m2bx1 != 0 || m.m2bx2 != 0) ? -1 : 0), a2 = R(-m.m3a4);
   // the next partner's five pair planes are loaded into registers while this partner is transformed
   cx<R> pre[5][KP];
-  // the five pass-A planes of pair (t, q): partners q < Q1 from the resident store ([target][Q1][5]), the
-  // others from the batch's own z stage ([t][P - Q1][5])
-  auto pairsrc = [&](int q) -> const cx<R>* {
-    return q < Q1 ? store + (long(fa.t0 + wg.t) * Q1 + q) * 5 * NR
-                  : buf5 + (long(wg.t) * (fa.P - Q1) + (q - Q1)) * 5 * NR;
+  // the five pass-A planes of pair (jt, q): from the resident store, square ([target][Q1][5], partners
+  // q < Q1) or triangular (tri: the pairs of q <= jt directly, those of q > jt as the reflected conjugate of
+  // (q, jt), cj, while jt < Q1); the others from the batch's own z stage ([t][P - Q1][5]; formed: it holds
+  // them for partners q >= Q1)
+  auto pairsrc = [&](int q, bool& cj) -> const cx<R>* {
+    cj = false;
+    if (tri) {
+      if (q <= jt && q < Q1) return store + (tri_row(jt, Q1) + q) * 5 * NR;
+      if (jt < Q1 && (q < Q1 || !formed)) {
+        cj = true;
+        return store + (tri_row(q, Q1) + jt) * 5 * NR;
+      }
+    } else if (q < Q1) {
+      return store + (long(jt) * Q1 + q) * 5 * NR;
+    }
+    return buf5 + (long(wg.t) * (fa.P - Q1) + (q - Q1)) * 5 * NR;
   };
+  // one load path for both cases (offsets and the sign of the imaginary part chosen per partner), so that
+  // the loads stay in flight together
   auto fetch = [&](int q) {
-    const gptr<cx<R>> src = uniform_global(pairsrc(q));
+    bool cj;
+    const gptr<cx<R>> src = uniform_global(pairsrc(q, cj));
+    const R sg = cj ? R(-1) : R(1);
+    unsigned o[KP];
+#pragma unroll
+    for (int i = 0; i < KP; ++i) o[i] = cj ? wg.flip(i) * unsigned(sizeof(cx<R>)) : ob[i];
 #pragma unroll
     for (int f = 0; f < 5; ++f)
 #pragma unroll
-      for (int i = 0; i < KP; ++i) pre[f][i] = ldo(src + f * NR, ob[i]);
+      for (int i = 0; i < KP; ++i) {
+        const cx<R> v = ldo(src + f * NR, o[i]);
+        pre[f][i] = mk<R>(v.x, sg * v.y);
+      }
   };
   if (PF && wg.qb < wg.qe) fetch(wg.qb);
   for (int q = wg.qb; q < wg.qe; ++q) {
@@ -1334,7 +1370,8 @@ k_fused_A(const cx<R>* buf5, const cx<R>* psi, const cx<R>* Dl, const cx<R>* Hl,
     const long pair = long(wg.t) * fa.P + q;
     const double* del = dfr + 3 * pair_dindex(mi, jt, q, 1);
     const R k1 = R(double(mfreq<N>(wg.x)) + del[0]);
-    const cx<R>* src = pairsrc(q);
+    bool cj;
+    const cx<R>* src = pairsrc(q, cj);
     const gptr<cx<R>> pq = uniform_global(psi + long(q) * NR);
     const gptr<cx<R>> dq = uniform_global(Dl + long(q) * NR);       // component d at dq + d P N^3
     const gptr<cx<R>> hq = uniform_global(Hl + long(q) * 3 * NR);   // component d at hq + d N^3
@@ -1349,8 +1386,10 @@ k_fused_A(const cx<R>* buf5, const cx<R>* psi, const cx<R>* Dl, const cx<R>* Hl,
       auto field = [&](int f, int i) -> cx<R> {
         if constexpr (PF || STAGE)
           return pre[f][i];
-        else
-          return src[f * NR + wg.zo + RB * N * i];
+        else {
+          const cx<R> v = src[f * NR + (cj ? wg.flip(i) : wg.zo + RB * N * i)];
+          return mk<R>(v.x, cj ? -v.y : v.y);
+        }
       };
       // load: slot 0 XV, slots 1-3 Y_par, slots ab..ab+2 Y_anti
 #pragma unroll
@@ -1511,7 +1550,8 @@ struct PassO {
 template <typename R, int N, bool SPLITH = false>
 __global__ void __launch_bounds__((Fz<R, N>::NTH)) k_fused_O(const cx<R>* buf4, const cx<R>* psi, const double* w,
                                                            FusedArgs fa, MeshInfo mi, Recip rc, const double* dfr,
-                                                           R* h5part, cx<R>* H3part, long sT = -1, long sQ = 4) {
+                                                           R* h5part, cx<R>* H3part, long sT = -1, long sQ = 4,
+                                                           const cx<R>* trs = nullptr, int Q1 = 0) {
   using F = Fz<R, N>;
   constexpr int KP = F::KP, RB = F::RB, PL = F::PLANE;
   constexpr bool SPLIT = PassO<R, N>::SPLIT;
@@ -1544,21 +1584,46 @@ __global__ void __launch_bounds__((Fz<R, N>::NTH)) k_fused_O(const cx<R>* buf4, 
     if constexpr (SPLITH) h5b[i] = R(0);
     H[i][0] = H[i][1] = H[i][2] = mk<R>(R(0), R(0));
   }
+  // fields 1..4 of the pair (row ja, partner q): at t sT + q sQ in buf4, or (trs, the triangular store of
+  // pass-A pairs) the stored pair (q, ja) of ja <= q, else the reflected conjugate (cj) of (ja, q)
+  auto pairsrc = [&](int q, bool& cj) -> const cx<R>* {
+    cj = false;
+    if (trs) {
+      if (ja <= q) return trs + ((tri_row(q, Q1) + ja) * 5 + 1) * NR;
+      cj = true;
+      return trs + ((tri_row(ja, Q1) + q) * 5 + 1) * NR;
+    }
+    return buf4 + (long(wg.t) * sT + long(q) * sQ) * NR;
+  };
+  // one load path for both cases: offsets and the sign of the imaginary part chosen per partner
+  auto ld = [&](const cx<R>* src, bool cj, int f, int i) -> cx<R> {
+    const cx<R> v = src[f * NR + (cj ? wg.flip(i) : wg.zo + RB * N * i)];
+    return mk<R>(v.x, cj ? -v.y : v.y);
+  };
   // the next partner's four pair planes are loaded into registers while this partner is transformed
   cx<R> pre[4][KP];
   auto fetch = [&](int q) {
-    const cx<R>* src = buf4 + (long(wg.t) * sT + long(q) * sQ) * NR + wg.zo;
+    bool cj;
+    const gptr<cx<R>> src = uniform_global(pairsrc(q, cj));
+    const R sg = cj ? R(-1) : R(1);
+    unsigned o[KP];
+#pragma unroll
+    for (int i = 0; i < KP; ++i) o[i] = (cj ? wg.flip(i) : wg.zo + RB * N * i) * unsigned(sizeof(cx<R>));
 #pragma unroll
     for (int f = 0; f < 4; ++f)
 #pragma unroll
-      for (int i = 0; i < KP; ++i) pre[f][i] = src[f * NR + RB * N * i];
+      for (int i = 0; i < KP; ++i) {
+        const cx<R> v = ldo(src + f * NR, o[i]);
+        pre[f][i] = mk<R>(v.x, sg * v.y);
+      }
   };
   if (PF && wg.qb < wg.qe) fetch(wg.qb);
   for (int q = wg.qb; q < wg.qe; ++q) {
     const R wq = R(w[q]);
     const double* del = dfr + 3 * pair_dindex(mi, ja, q, 0);
     const R k1 = R(double(mfreq<N>(wg.x)) + del[0]);
-    const cx<R>* src = buf4 + (long(wg.t) * sT + long(q) * sQ) * NR + wg.zo;
+    bool cj;
+    const cx<R>* src = pairsrc(q, cj);
 #pragma unroll 1
     for (int g = 0; g < (SPLIT ? 2 : 1); ++g) {
       const bool par = !SPLIT || g == 0, anti = !SPLIT || g == 1;
@@ -1566,19 +1631,18 @@ __global__ void __launch_bounds__((Fz<R, N>::NTH)) k_fused_O(const cx<R>* buf4, 
 #pragma unroll
       for (int i = 0; i < KP; ++i) {
         const int so = wg.so0 + RB * F::LD * i;
-        const long o = RB * N * i;
         const R k2 = R(double(mfreq<N>(wg.y0 + RB * i)) + del[1]);
         if (par) {
-          const cx<R> w0 = !PF ? src[o] : pre[0][i];
+          const cx<R> w0 = !PF ? ld(src, cj, 0, i) : pre[0][i];
           sm[so] = mul_i(k1 * w0);
           sm[PL + so] = mul_i(k2 * w0);
-          sm[2 * PL + so] = !PF ? src[NR + o] : pre[1][i];
+          sm[2 * PL + so] = !PF ? ld(src, cj, 1, i) : pre[1][i];
         }
         if (anti) {
-          const cx<R> w0 = !PF ? src[2 * NR + o] : pre[2][i];
+          const cx<R> w0 = !PF ? ld(src, cj, 2, i) : pre[2][i];
           sm[ab * PL + so] = mul_i(k1 * w0);
           sm[(ab + 1) * PL + so] = mul_i(k2 * w0);
-          sm[(ab + 2) * PL + so] = !PF ? src[3 * NR + o] : pre[3][i];
+          sm[(ab + 2) * PL + so] = !PF ? ld(src, cj, 3, i) : pre[3][i];
         }
       }
       if (PF && q + 1 < wg.qe) fetch(q + 1);

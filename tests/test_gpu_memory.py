@@ -90,8 +90,8 @@ def relerr(a, b):
 
 
 def _store_budget(w, q1, elem_bytes, bitc=False):
-    """Caller budget at which the resident store holds q1 partner columns of every target: a batch of 8
-    targets of pair buffers plus q1 columns of 5 fields (one spin channel)."""
+    """Caller budget of a batch of 8 targets of pair buffers plus q1 full partner columns of 5 fields (one
+    spin channel): the triangular store of TC mode fits q1 columns in it and not q1 + 1 (P > q1 (q1 + 1) / 2)."""
     P, NR = w.nk * w.nband, int(np.prod(w.grid))
     per_target = P * ((8 if bitc else 5) + 4) * NR * elem_bytes
     return per_target * min(8, P) + q1 * 5 * P * NR * elem_bytes
@@ -99,10 +99,12 @@ def _store_budget(w, q1, elem_bytes, bitc=False):
 
 @pytest.mark.parametrize("prec,elem", [("fp64", 16), ("fp32", 8)])
 def test_partial_pair_store_equals_no_store(prec, elem):
-    """A caller budget between an eighth and all of the store: the store keeps the first Q1 partner columns;
-    the occupied pass reads them for its rows below Q1 and forms its own pairs for the others, and pass A
-    forms the pairs of the other partners.  Same operator, energy and orbital energies as without the store
-    (to rounding), and as the oracle; the occupied pass's own pair densities run for some rows only."""
+    """A caller budget between an eighth and all of the store: the triangular store keeps the first Q1 = 3
+    partner columns (the pairs (t, q) of q <= t, q < 3; the others of min(t, q) < 3 read reflected and
+    conjugated); the occupied pass reads them for its rows below Q1 and forms its own pairs for the others,
+    and pass A forms the pairs of targets and partners at or above Q1.  Same operator, energy and orbital
+    energies as without the store (to rounding), and as the oracle; the occupied pass's own pair densities
+    run for some rows only."""
     from oracle.fftroute import ALL_TERMS, MULT, Problem
 
     w = T.tiny_fcc(kmesh=(2, 2, 1), grid=12, ecut=2.0, nb=2, a=6.0, occ=[1.0, 0.8])
@@ -173,19 +175,20 @@ def _refusing_op(w, cap, refused, budget=0, batch=0, pair_store=True):
 
 
 def test_store_takes_fewer_columns_when_an_allocation_fails():
-    """An allocator that refuses every request above 12 MB: the whole store (20 MB in FP64) is refused, and
-    the store settles on the most partner columns that it grants (7 of 12); the next application asks for
-    no refused size again.  The operator equals the one without the store."""
+    """An allocator that refuses every request above 8 MiB: the whole triangular store (78 pairs, 10.8 MB in
+    FP64) is refused, and the store settles on the most partner columns that it grants (6 of 12: 57 pairs,
+    7.9 MB); the next application asks for no refused size again.  The operator equals the one without the
+    store."""
     w = _case()
     P = w.nk * w.nband
-    _say("[gpu] pair store under an allocator that refuses requests above 12 MB")
+    _say("[gpu] pair store under an allocator that refuses requests above 8 MiB")
     ref = tc.from_workload(w, precision=tc.TC_PREC_FP64, pair_store=False, batch=4)
     ref.set_profiling(True)
     ref.kernel_stats(reset=True)
     hc_ref = ref.apply()
     own_ref = ref.kernel_stats()["k_pair_xy<R,N,true>"]["launches"]
     ref.close()
-    cap, refused = 12 << 20, []
+    cap, refused = 8 << 20, []
     op = _refusing_op(w, cap, refused, budget=64 << 20, batch=4)
     op.set_profiling(True)
     outs = []
@@ -193,12 +196,12 @@ def test_store_takes_fewer_columns_when_an_allocation_fails():
         op.kernel_stats(reset=True)
         outs.append((op.apply(), op.kernel_stats()["k_pair_xy<R,N,true>"]["launches"], len(refused)))
     op.close()
-    col = 5 * P * int(np.prod(w.grid)) * 16
-    _say(f"    refused {[r // col for r in refused]} columns; own occupied-pass pair launches "
+    pair = 5 * int(np.prod(w.grid)) * 16
+    _say(f"    refused {[r // pair for r in refused]} pairs; own occupied-pass pair launches "
          f"{[o[1] for o in outs]} (without the store {own_ref})")
-    assert refused and all(r > cap for r in refused) and P * col in refused
+    assert refused and all(r > cap for r in refused) and P * (P + 1) // 2 * pair in refused
     assert outs[1][2] == outs[0][2]                         # no refused size asked for again
-    assert own_ref == 3 and outs[0][1] == outs[1][1] == 2   # rows 7-10 and 11 form their own pairs
+    assert own_ref == 3 and outs[0][1] == outs[1][1] == 2   # rows 6-9 and 10-11 form their own pairs
     for hc, _, _ in outs:
         assert relerr(hc, hc_ref) < 1e-12
 
