@@ -1600,18 +1600,10 @@ struct EngineT : Engine {
                                fa, bufA.p);
           });
           const long rows = tri_row(t0 + nt, Q1) - tri_row(t0, Q1);   // pairs the batch's rows hold
-          K(TC_K_ZCONV_A1, fb * 6.0 * rows + tabB, [&] {
-            if (t0 >= Q1) {   // Q1 pairs in every row
-              const MeshInfo miQ{pb.n1, pb.n2, pb.n3, nb, Q1, nb};
-              zconv<OP_A1>(s, bufA.p, store(c) + size_t(tri_row(t0, Q1)) * 5 * NR, long(nt) * Q1, t0, miQ, tb, 1);
-            } else {
-              for (int t = 0; t < nt; ++t) {   // row t0 + t: partners 0 .. min(t0 + t, Q1 - 1)
-                const int L = std::min(t0 + t + 1, Q1);
-                const MeshInfo miL{pb.n1, pb.n2, pb.n3, nb, L, nb};
-                zconv<OP_A1>(s, bufA.p + size_t(t) * qn * NR, store(c) + size_t(tri_row(t0 + t, Q1)) * 5 * NR, L,
-                             t0 + t, miL, tb, 1);
-              }
-            }
+          K(TC_K_ZCONV_A1, fb * 6.0 * rows + tabB, [&] {   // row t0 + t: partners 0 .. min(t0 + t, Q1 - 1)
+            MeshInfo miQ{pb.n1, pb.n2, pb.n3, nb, qn, nb};
+            miQ.trq = Q1;
+            zconv<OP_A1>(s, bufA.p, store(c) + size_t(tri_row(t0, Q1)) * 5 * NR, rows, t0, miQ, tb, 1);
           });
         }
     } else if (keepA) {   // the pairs (t, q < Q1) of every target, before the occupied pass

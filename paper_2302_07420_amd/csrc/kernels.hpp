@@ -29,6 +29,7 @@ struct MeshInfo {
   const int* tk = nullptr;   // k-point of target block j / nbt (device; null: the block index itself)
   int nkb = 0;               // band k-points, coded nk .. nk + nkb - 1 in tk
   int qoff = 0;              // partner q of a pass is orbital q + qoff (a pass over partners qoff .. P - 1)
+  int trq = 0;               // z stage: > 0, the rows of a triangular store with Q1 = trq (pair_tq)
 };
 
 __device__ __forceinline__ int kindex_delta(const MeshInfo& mi, int kto, int kfrom) {
@@ -349,6 +350,29 @@ struct FusedArgs {
 // conjugate of (q, t)'s at the reflected xy frequencies (-Gx, -Gy).  Offset (in pairs) of row t:
 __host__ __device__ __forceinline__ long tri_row(int t, int Q1) {
   return t < Q1 ? long(t) * (t + 1) / 2 : long(Q1) * (Q1 + 1) / 2 + long(t - Q1) * Q1;
+}
+
+// Pair p of a z-stage launch -> its row t of the batch and partner q.  Rectangular batches have rows of mi.P
+// pairs.  A triangular one (mi.trq > 0) is the rows t0 + t of the triangular store with Q1 = trq, of
+// min(t0 + t + 1, trq) pairs each, one after another; its input rows (the batch's pair planes) hold mi.P.
+__device__ __forceinline__ void pair_tq(const MeshInfo& mi, int t0, long p, int& t, int& q) {
+  if (mi.trq <= 0) {
+    t = int(p / mi.P);
+    q = int(p - long(t) * mi.P);
+    return;
+  }
+  const long Q = mi.trq, g = tri_row(t0, mi.trq) + p, full = Q * (Q + 1) / 2;
+  long r;
+  if (g < full) {   // row r holds the pairs r (r + 1) / 2 .. (r + 1) (r + 2) / 2 - 1
+    r = long((sqrt(8.0 * double(g) + 1.0) - 1.0) * 0.5);
+    while (r * (r + 1) / 2 > g) --r;
+    while ((r + 1) * (r + 2) / 2 <= g) ++r;
+    q = int(g - r * (r + 1) / 2);
+  } else {
+    r = Q + (g - full) / Q;
+    q = int(g - full - (r - Q) * Q);
+  }
+  t = int(r) - t0;
 }
 
 // index of the pair's shift in the kernel tables: k_jt - k_q (sign 1, target passes) or k_q - k_jt (sign 0);
@@ -828,7 +852,8 @@ k_zconv(const cx<R>* in, cx<R>* out, long npairs, int t0, MeshInfo mi, Tables tb
   if (col >= npairs * NN) return;
   const long pair = col / NN;
   const int xy = int(col - pair * NN);
-  const int t = int(pair / mi.P), q = int(pair - long(t) * mi.P);
+  int t, q;
+  pair_tq(mi, t0, pair, t, q);
   const int di = pair_dindex(mi, t0 + t, q, sign_target_minus_partner);
   const R* tV = reinterpret_cast<const R*>(tb.V) + long(di) * NR + xy;
   const R* tU[2] = {reinterpret_cast<const R*>(tb.U1) + long(di) * NR + xy,
@@ -837,7 +862,7 @@ k_zconv(const cx<R>* in, cx<R>* out, long npairs, int t0, MeshInfo mi, Tables tb
 
   if constexpr (NIN == 1) {
     cx<R> acc[N], v[N];
-    const cx<R>* b = in + pair * NR + xy;
+    const cx<R>* b = in + (long(t) * mi.P + q) * NR + xy;
 #pragma unroll
     for (int z = 0; z < N; ++z) acc[z] = b[z * NN];
     fft_line<R, N, -1>(acc);
@@ -970,7 +995,8 @@ k_zconv48(const cx<R>* in, cx<R>* out, long npairs, int t0, MeshInfo mi, Tables 
   if (col >= npairs * NN) return;
   const long pair = col / NN;
   const int xy = int(col - pair * NN);
-  const int t = int(pair / mi.P), q = int(pair - long(t) * mi.P);
+  int t, q;
+  pair_tq(mi, t0, pair, t, q);
   const int di = pair_dindex(mi, t0 + t, q, sign_target_minus_partner);
   // frequency of element j after the forward half: k = 2 j + h; real-space z = 24 h + j
   const long kof = long(di) * NR + xy + (h ? NN : 0);
@@ -984,7 +1010,7 @@ k_zconv48(const cx<R>* in, cx<R>* out, long npairs, int t0, MeshInfo mi, Tables 
 
   if constexpr (NIN == 1) {
     cx<R> acc[H], v[H];
-    const cx<R>* b = in + pair * NR + xy + zo;
+    const cx<R>* b = in + (long(t) * mi.P + q) * NR + xy + zo;
 #pragma unroll
     for (int j = 0; j < H; ++j) acc[j] = b[j * NN];
     fwd48_pair(acc, hf);
@@ -1181,8 +1207,14 @@ k_zconv_mfma(const cx<float>* in, cx<float>* out, long npairs, int t0, MeshInfo 
     long pair;
     int xy;
     col_base(grp, pair, xy);
+    if constexpr (NIN == 1) {
+      int tt, qq;
+      pair_tq(mi, t0, pair, tt, qq);
+      load_col(in + (long(tt) * mi.P + qq) * NR + xy, pre[0]);
+    } else {
 #pragma unroll
-    for (int c = 0; c < NIN; ++c) load_col(in + (pair * NIN + c) * NR + xy, pre[c]);
+      for (int c = 0; c < NIN; ++c) load_col(in + (pair * NIN + c) * NR + xy, pre[c]);
+    }
     if constexpr (OP == OP_A2) {
       if (inB) {   // parallel inputs minus the pass-B sources
 #pragma unroll
@@ -1203,7 +1235,8 @@ k_zconv_mfma(const cx<float>* in, cx<float>* out, long npairs, int t0, MeshInfo 
     col_base(grp, pair, xy);
     if (!kPrefetch) fetch(grp);
     const bool more = kPrefetch && grp + stride < ngroups;
-    const int t = int(pair / mi.P), q = int(pair - long(t) * mi.P);
+    int t, q;
+    pair_tq(mi, t0, pair, t, q);
     const int di = pair_dindex(mi, t0 + t, q, sign_target_minus_partner);
     const float* tV = reinterpret_cast<const float*>(tb.V) + long(di) * NR + xy;
     const float* tU[2] = {reinterpret_cast<const float*>(tb.U1) + long(di) * NR + xy,
