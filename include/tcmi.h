@@ -411,19 +411,23 @@ int tc_last_timing(tc_ctx* ctx, double* total_ms, double* stage_ms, int n);
 int tc_set_batch(tc_ctx* ctx, int targets_per_batch);
 
 /* Resident pair store (on = 1, the default): when tc_apply_all* runs with the orbitals as targets,
- * the pass-A z-stage outputs of the pairs (t, q) of every target t and of the first Q1 partners q
- * (5 Q1 P fields of N1 N2 N3 working-precision complex values per spin channel) are computed once
- * and kept, and the occupied-occupied pass reads its four fields per pair from them for its rows
- * a < Q1 (the pair (a, b) of that pass is the pass-A pair with target b and partner a: same density
- * conj(chi_a) psi_b, same momentum k_b - k_a; in the biorthogonal mode its second convolution, of
- * conj(chi_b) psi_a at k_a - k_b, is the pass-A pair with target a and partner b) instead of
- * recomputing them; pass A then forms only the pairs of the partners q >= Q1.  Q1 = P when every
- * pair fits; otherwise as many partner columns as fit with an eighth of the device's memory (at
- * least 16 GiB) left free after the batch buffers, and none when fewer than P/8 fit (the
- * biorthogonal mode stores every pair or none).  With a budget (tc_set_memory_budget) the store
- * takes what is left of it after 8 targets of pair buffers.  With on = 0 both passes transform their
- * own pair densities.  Results do not depend on it; the store is released when it is switched off.
- * Trial vectors, band k-points and symmetry-reduced runs always use the batched form. */
+ * the pass-A z-stage outputs of the orbital pairs (5 fields of N1 N2 N3 working-precision complex values
+ * per pair and spin channel) are computed once, before the occupied-occupied pass, and kept.  The pair
+ * (a, b) of that pass is the pass-A pair with target b and partner a (same density conj(chi_a) psi_b,
+ * same momentum k_b - k_a), so the pass reads its four fields per pair from the store instead of
+ * recomputing them.  TC mode keeps only the pairs (t, q) with q <= t, in triangular rows: the pair
+ * (t, q) of q > t is the conjugate of (q, t)'s output at the reflected xy frequencies (its density is
+ * the conjugate and its shift the negative, and every kernel is real in real space and zero on the
+ * Nyquist planes).  Where not every pair fits, the store keeps the first Q1 partner columns (the pairs
+ * with min(t, q) < Q1): the occupied pass forms its own pairs for its rows a >= Q1 and pass A those of
+ * the targets and partners at or above Q1.  Q1 is as many columns as fit with an eighth of the
+ * device's memory (at least 16 GiB) left free after the batch buffers, and none when fewer than P/8
+ * fit.  The biorthogonal mode needs both orders of a pair (conj(chi_b) psi_a at k_a - k_b is the
+ * pass-A pair with target a and partner b) and stores all P^2 pairs or none.  With a budget
+ * (tc_set_memory_budget) the store takes what is left of it after 8 targets of pair buffers.  With on
+ * = 0 both passes transform their own pair densities.  Results do not depend on it; the store is
+ * released when it is switched off.  Trial vectors, band k-points and symmetry-reduced runs always
+ * use the batched form. */
 int tc_set_pair_store(tc_ctx* ctx, int on);
 
 /* Kernels timed by tc_kernel_stats (device time between HIP events recorded on the
