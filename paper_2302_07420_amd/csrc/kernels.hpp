@@ -347,7 +347,9 @@ struct FusedArgs {
 // q < Q1, min(t + 1, Q1) of them, rows one after another.  The pair (t, q) of q > t is read from the pair
 // (q, t): its density is the conjugate of (t, q)'s and its shift the negative, and every kernel that
 // multiplies it is real in real space and zero on the Nyquist planes, so its z-stage output is the
-// conjugate of (q, t)'s at the reflected xy frequencies (-Gx, -Gy).  Offset (in pairs) of row t:
+// conjugate of (q, t)'s at the reflected frequencies, and every field that the plane kernels form from it
+// (with its own shift) and transform to real space is the conjugate of (q, t)'s.  The plane kernels load
+// (q, t) as it is, transform it with (q, t)'s shift and conjugate in real space.  Offset (in pairs) of row t:
 __host__ __device__ __forceinline__ long tri_row(int t, int Q1) {
   return t < Q1 ? long(t) * (t + 1) / 2 : long(Q1) * (Q1 + 1) / 2 + long(t - Q1) * Q1;
 }
@@ -682,11 +684,6 @@ struct PlaneWG {
       return sigma48(y0 + F::RB * i) * F::LD + sx;
     else
       return so(i);
-  }
-  // element offset within a volume of owned point i reflected through the xy origin, (-y, -x) mod N
-  __device__ __forceinline__ unsigned flip(int i) const {
-    const int y = y0 + F::RB * i;
-    return unsigned(z * N * N + (y == 0 ? 0 : N - y) * N + (x == 0 ? 0 : N - x));
   }
   // between a round's reads at ss() and the next round's writes at so(): a barrier where they differ
   __device__ __forceinline__ void end_round() const {
@@ -1364,9 +1361,9 @@ k_fused_A(const cx<R>* buf5, const cx<R>* psi, const cx<R>* Dl, const cx<R>* Hl,
   // the next partner's five pair planes are loaded into registers while this partner is transformed
   cx<R> pre[5][KP];
   // the five pass-A planes of pair (jt, q): from the resident store, square ([target][Q1][5], partners
-  // q < Q1) or triangular (tri: the pairs of q <= jt directly, those of q > jt as the reflected conjugate of
-  // (q, jt), cj, while jt < Q1); the others from the batch's own z stage ([t][P - Q1][5]; formed: it holds
-  // them for partners q >= Q1)
+  // q < Q1) or triangular (tri: the pairs of q <= jt directly, those of q > jt through (q, jt), cj, while
+  // jt < Q1); the others from the batch's own z stage ([t][P - Q1][5]; formed: it holds them for partners
+  // q >= Q1)
   auto pairsrc = [&](int q, bool& cj) -> const cx<R>* {
     cj = false;
     if (tri) {
@@ -1380,22 +1377,16 @@ k_fused_A(const cx<R>* buf5, const cx<R>* psi, const cx<R>* Dl, const cx<R>* Hl,
     }
     return buf5 + (long(wg.t) * (fa.P - Q1) + (q - Q1)) * 5 * NR;
   };
-  // one load path for both cases (offsets and the sign of the imaginary part chosen per partner), so that
-  // the loads stay in flight together
+  // A reflected pair (cj) is loaded as the stored pair (q, jt) itself and transformed with that pair's
+  // shift (the negative of (jt, q)'s): its real-space fields are the conjugates of (jt, q)'s, and are
+  // conjugated where they are read after the inverse transforms.  The loads are the same for both cases.
   auto fetch = [&](int q) {
     bool cj;
     const gptr<cx<R>> src = uniform_global(pairsrc(q, cj));
-    const R sg = cj ? R(-1) : R(1);
-    unsigned o[KP];
-#pragma unroll
-    for (int i = 0; i < KP; ++i) o[i] = cj ? wg.flip(i) * unsigned(sizeof(cx<R>)) : ob[i];
 #pragma unroll
     for (int f = 0; f < 5; ++f)
 #pragma unroll
-      for (int i = 0; i < KP; ++i) {
-        const cx<R> v = ldo(src + f * NR, o[i]);
-        pre[f][i] = mk<R>(v.x, sg * v.y);
-      }
+      for (int i = 0; i < KP; ++i) pre[f][i] = ldo(src + f * NR, ob[i]);
   };
   if (PF && wg.qb < wg.qe) fetch(wg.qb);
   for (int q = wg.qb; q < wg.qe; ++q) {
@@ -1405,6 +1396,13 @@ k_fused_A(const cx<R>* buf5, const cx<R>* psi, const cx<R>* Dl, const cx<R>* Hl,
     const R k1 = R(double(mfreq<N>(wg.x)) + del[0]);
     bool cj;
     const cx<R>* src = pairsrc(q, cj);
+    const double dsg = cj ? -1.0 : 1.0;   // shift of the loaded pair relative to (jt, q)
+    const R k1l = R(double(mfreq<N>(wg.x)) + dsg * del[0]);
+    // a value of the inverse-transformed planes, conjugated for a reflected pair
+    auto rd = [&](int idx) {
+      const cx<R> v = sm[idx];
+      return mk<R>(v.x, cj ? -v.y : v.y);
+    };
     const gptr<cx<R>> pq = uniform_global(psi + long(q) * NR);
     const gptr<cx<R>> dq = uniform_global(Dl + long(q) * NR);       // component d at dq + d P N^3
     const gptr<cx<R>> hq = uniform_global(Hl + long(q) * 3 * NR);   // component d at hq + d N^3
@@ -1419,27 +1417,25 @@ k_fused_A(const cx<R>* buf5, const cx<R>* psi, const cx<R>* Dl, const cx<R>* Hl,
       auto field = [&](int f, int i) -> cx<R> {
         if constexpr (PF || STAGE)
           return pre[f][i];
-        else {
-          const cx<R> v = src[f * NR + (cj ? wg.flip(i) : wg.zo + RB * N * i)];
-          return mk<R>(v.x, cj ? -v.y : v.y);
-        }
+        else
+          return src[f * NR + wg.zo + RB * N * i];
       };
       // load: slot 0 XV, slots 1-3 Y_par, slots ab..ab+2 Y_anti
 #pragma unroll
       for (int i = 0; i < KP; ++i) {
         const int so = wg.so0 + RB * F::LD * i;
-        const R k2 = R(double(mfreq<N>(wg.y0 + RB * i)) + del[1]);
+        const R k2l = R(double(mfreq<N>(wg.y0 + RB * i)) + dsg * del[1]);
         if (par) {
           sm[so] = field(0, i);
           const cx<R> w0 = field(1, i);
-          sm[PL + so] = mul_i(k1 * w0);
-          sm[2 * PL + so] = mul_i(k2 * w0);
+          sm[PL + so] = mul_i(k1l * w0);
+          sm[2 * PL + so] = mul_i(k2l * w0);
           sm[3 * PL + so] = field(2, i);
         }
         if (anti) {
           const cx<R> w0 = field(3, i);
-          sm[ab * PL + so] = mul_i(k1 * w0);
-          sm[(ab + 1) * PL + so] = mul_i(k2 * w0);
+          sm[ab * PL + so] = mul_i(k1l * w0);
+          sm[(ab + 1) * PL + so] = mul_i(k2l * w0);
           sm[(ab + 2) * PL + so] = field(4, i);
         }
       }
@@ -1452,10 +1448,10 @@ k_fused_A(const cx<R>* buf5, const cx<R>* psi, const cx<R>* Dl, const cx<R>* Hl,
         const int so = wg.ss(i);
         if (par) {
           const cx<R> p = ldo(pq, ob[i]);
-          cfma(ga[i][0], a0 * wq, sm[so], p);
+          cfma(ga[i][0], a0 * wq, rd(so), p);
           cx<R> Y[3];
 #pragma unroll
-          for (int d = 0; d < 3; ++d) Y[d] = sm[(1 + d) * PL + so];
+          for (int d = 0; d < 3; ++d) Y[d] = rd((1 + d) * PL + so);
           // the two dot products are summed over d before their weights are applied
           cx<R> sD = Y[0] * ldo(dq, ob[i]), sH = Y[0] * ldo(hq, ob[i]);
 #pragma unroll
@@ -1480,7 +1476,7 @@ k_fused_A(const cx<R>* buf5, const cx<R>* psi, const cx<R>* Dl, const cx<R>* Hl,
             nanti = nk[i];
 #pragma unroll
           for (int d = 0; d < 3; ++d) {
-            const cx<R> y = sm[(ab + d) * PL + so];
+            const cx<R> y = rd((ab + d) * PL + so);
             sm[(ab + d) * PL + so] = CN ? y * nanti : nanti.x * y;
           }
         }
@@ -1618,7 +1614,8 @@ __global__ void __launch_bounds__((Fz<R, N>::NTH)) k_fused_O(const cx<R>* buf4, 
     H[i][0] = H[i][1] = H[i][2] = mk<R>(R(0), R(0));
   }
   // fields 1..4 of the pair (row ja, partner q): at t sT + q sQ in buf4, or (trs, the triangular store of
-  // pass-A pairs) the stored pair (q, ja) of ja <= q, else the reflected conjugate (cj) of (ja, q)
+  // pass-A pairs) the stored pair (q, ja) of ja <= q, else (cj) the stored pair (ja, q), which is loaded as it
+  // is, transformed with its own shift (the negative) and conjugated in real space where it is read
   auto pairsrc = [&](int q, bool& cj) -> const cx<R>* {
     cj = false;
     if (trs) {
@@ -1628,35 +1625,25 @@ __global__ void __launch_bounds__((Fz<R, N>::NTH)) k_fused_O(const cx<R>* buf4, 
     }
     return buf4 + (long(wg.t) * sT + long(q) * sQ) * NR;
   };
-  // one load path for both cases: offsets and the sign of the imaginary part chosen per partner
-  auto ld = [&](const cx<R>* src, bool cj, int f, int i) -> cx<R> {
-    const cx<R> v = src[f * NR + (cj ? wg.flip(i) : wg.zo + RB * N * i)];
-    return mk<R>(v.x, cj ? -v.y : v.y);
-  };
+  auto ld = [&](const cx<R>* src, int f, int i) -> cx<R> { return src[f * NR + wg.zo + RB * N * i]; };
   // the next partner's four pair planes are loaded into registers while this partner is transformed
   cx<R> pre[4][KP];
   auto fetch = [&](int q) {
     bool cj;
     const gptr<cx<R>> src = uniform_global(pairsrc(q, cj));
-    const R sg = cj ? R(-1) : R(1);
-    unsigned o[KP];
-#pragma unroll
-    for (int i = 0; i < KP; ++i) o[i] = (cj ? wg.flip(i) : wg.zo + RB * N * i) * unsigned(sizeof(cx<R>));
 #pragma unroll
     for (int f = 0; f < 4; ++f)
 #pragma unroll
-      for (int i = 0; i < KP; ++i) {
-        const cx<R> v = ldo(src + f * NR, o[i]);
-        pre[f][i] = mk<R>(v.x, sg * v.y);
-      }
+      for (int i = 0; i < KP; ++i) pre[f][i] = ldo(src + f * NR, (wg.zo + RB * N * i) * unsigned(sizeof(cx<R>)));
   };
   if (PF && wg.qb < wg.qe) fetch(wg.qb);
   for (int q = wg.qb; q < wg.qe; ++q) {
     const R wq = R(w[q]);
     const double* del = dfr + 3 * pair_dindex(mi, ja, q, 0);
-    const R k1 = R(double(mfreq<N>(wg.x)) + del[0]);
     bool cj;
     const cx<R>* src = pairsrc(q, cj);
+    const double dsg = cj ? -1.0 : 1.0;   // shift of the loaded pair relative to (q, ja)
+    const R k1 = R(double(mfreq<N>(wg.x)) + dsg * del[0]);
 #pragma unroll 1
     for (int g = 0; g < (SPLIT ? 2 : 1); ++g) {
       const bool par = !SPLIT || g == 0, anti = !SPLIT || g == 1;
@@ -1664,18 +1651,18 @@ __global__ void __launch_bounds__((Fz<R, N>::NTH)) k_fused_O(const cx<R>* buf4, 
 #pragma unroll
       for (int i = 0; i < KP; ++i) {
         const int so = wg.so0 + RB * F::LD * i;
-        const R k2 = R(double(mfreq<N>(wg.y0 + RB * i)) + del[1]);
+        const R k2 = R(double(mfreq<N>(wg.y0 + RB * i)) + dsg * del[1]);
         if (par) {
-          const cx<R> w0 = !PF ? ld(src, cj, 0, i) : pre[0][i];
+          const cx<R> w0 = !PF ? ld(src, 0, i) : pre[0][i];
           sm[so] = mul_i(k1 * w0);
           sm[PL + so] = mul_i(k2 * w0);
-          sm[2 * PL + so] = !PF ? ld(src, cj, 1, i) : pre[1][i];
+          sm[2 * PL + so] = !PF ? ld(src, 1, i) : pre[1][i];
         }
         if (anti) {
-          const cx<R> w0 = !PF ? ld(src, cj, 2, i) : pre[2][i];
+          const cx<R> w0 = !PF ? ld(src, 2, i) : pre[2][i];
           sm[ab * PL + so] = mul_i(k1 * w0);
           sm[(ab + 1) * PL + so] = mul_i(k2 * w0);
-          sm[(ab + 2) * PL + so] = !PF ? ld(src, cj, 3, i) : pre[3][i];
+          sm[(ab + 2) * PL + so] = !PF ? ld(src, 3, i) : pre[3][i];
         }
       }
       if (PF && q + 1 < wg.qe) fetch(q + 1);
@@ -1693,7 +1680,7 @@ __global__ void __launch_bounds__((Fz<R, N>::NTH)) k_fused_O(const cx<R>* buf4, 
           h5[i] += wq * norm2(Y);
 #pragma unroll
           for (int d = 0; d < 3; ++d) {
-            const cx<R> hv = cmulc(Y[d], pq);
+            const cx<R> hv = cmulc(mk<R>(Y[d].x, cj ? -Y[d].y : Y[d].y), pq);   // Y conjugated when reflected
             H[i][d].x += wq * hv.x;
             H[i][d].y += wq * hv.y;
           }
