@@ -385,15 +385,24 @@ def test_bitc_polarized_scf_with_equal_channels_follows_the_unpolarized_loop():
 @pytest.mark.parametrize("name", ["fcc_k221_g12_pol_empty_band", "fcc_k211_g8_bitc_pol"])
 def test_polarized_pair_store_on_and_off_agree(name):
     """Two channels with the resident store of pass-A z-stage outputs (one region per channel, read by the
-    occupied pass and pass A) and without it (each pass forms its own pairs): the same operator."""
+    occupied pass and pass A), with a budget that leaves it half of the partner columns (TC mode: the
+    triangular store of P/2 columns per channel; the biorthogonal mode then keeps none), and without it
+    (each pass forms its own pairs): the same operator."""
     w = CASES[name]()
-    _say(f"[gpu] polarised {name}: pair store on / off")
+    P, NR = w.nk * w.nband, int(np.prod(w.grid))
+    bitc = w.left is not None
+    keep = P * ((8 if bitc else 5) + 4) * NR * 16 * min(8, P)
+    q1 = P // 2
+    tri = q1 * (q1 + 1) // 2 + (P - q1) * q1
+    half = keep + 5 * 2 * NR * 16 * (P * q1 if bitc else tri)
+    _say(f"[gpu] polarised {name}: pair store on / half / off")
     res = []
-    for store in (True, False):
-        op = tc.from_workload(w, precision=tc.TC_PREC_FP64, pair_store=store)
+    for kw in (dict(), dict(mem_budget=half), dict(pair_store=False)):
+        op = tc.from_workload(w, precision=tc.TC_PREC_FP64, **kw)
         res.append((op.apply(), op.energy()[0], op.orbital_energies()))
         op.close()
-    for s in (0, 1):
-        assert relerr(res[1][0][s], res[0][0][s]) < 1e-12
-    assert abs(res[1][1] - res[0][1]) < 1e-12 * abs(res[0][1])
-    assert np.abs(res[1][2] - res[0][2]).max() < 1e-12 * np.abs(res[0][2]).max()
+    for r in res[1:]:
+        for s in (0, 1):
+            assert relerr(r[0][s], res[0][0][s]) < 1e-12
+        assert abs(r[1] - res[0][1]) < 1e-12 * abs(res[0][1])
+        assert np.abs(r[2] - res[0][2]).max() < 1e-12 * np.abs(res[0][2]).max()
