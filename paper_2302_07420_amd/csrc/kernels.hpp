@@ -636,6 +636,15 @@ __device__ __forceinline__ gptr<T> uniform_global(const T* p) {
   const unsigned hi = __builtin_amdgcn_readfirstlane(unsigned(v >> 32));
   return reinterpret_cast<gptr<T>>((static_cast<unsigned long long>(hi) << 32) | lo);
 }
+// A value at a wave-uniform address of a table that no kernel writes, read with a scalar load (into
+// scalar registers, without waiting on the vector memory counter)
+template <typename T>
+__device__ __forceinline__ T ld_uniform(const T* p) {
+  const unsigned long long v = reinterpret_cast<unsigned long long>(p);
+  const unsigned lo = __builtin_amdgcn_readfirstlane(unsigned(v));
+  const unsigned hi = __builtin_amdgcn_readfirstlane(unsigned(v >> 32));
+  return *reinterpret_cast<const __attribute__((address_space(4))) T*>((static_cast<unsigned long long>(hi) << 32) | lo);
+}
 template <typename R>
 __device__ __forceinline__ cx<R> ldo(gptr<cx<R>> base, unsigned byteoff) {
   typedef R v2 __attribute__((ext_vector_type(2)));
@@ -802,7 +811,8 @@ k_passB_xy(const cx<R>* psi, const cx<R>* chi, const cx<R>* Zl, const cx<R>* Hl,
     planes_fft<R, N, -1, true>(sm, 3 * nq, threadIdx.x);
     for (int a = 0; a < nq; ++a) {
       const int q = q0 + a;
-      const double* del = dfr + 3 * pair_dindex(mi, int(jt), q, 1);
+      const double* dl = dfr + 3 * pair_dindex(mi, int(jt), q, 1);
+      const double del[2] = {ld_uniform(dl), ld_uniform(dl + 1)};
       const R k1 = R(double(mfreq<N>(wg.x)) + del[0]);
       cx<R>* dst = out + (long(wg.t) * fa.P + q) * 2 * NR;
 #pragma unroll
@@ -1392,7 +1402,8 @@ k_fused_A(const cx<R>* buf5, const cx<R>* psi, const cx<R>* Dl, const cx<R>* Hl,
   for (int q = wg.qb; q < wg.qe; ++q) {
     const R wq = R(w[q]);
     const long pair = long(wg.t) * fa.P + q;
-    const double* del = dfr + 3 * pair_dindex(mi, jt, q, 1);
+    const double* dl = dfr + 3 * pair_dindex(mi, jt, q, 1);
+    const double del[2] = {ld_uniform(dl), ld_uniform(dl + 1)};
     const R k1 = R(double(mfreq<N>(wg.x)) + del[0]);
     bool cj;
     const cx<R>* src = pairsrc(q, cj);
@@ -1639,7 +1650,8 @@ __global__ void __launch_bounds__((Fz<R, N>::NTH)) k_fused_O(const cx<R>* buf4, 
   if (PF && wg.qb < wg.qe) fetch(wg.qb);
   for (int q = wg.qb; q < wg.qe; ++q) {
     const R wq = R(w[q]);
-    const double* del = dfr + 3 * pair_dindex(mi, ja, q, 0);
+    const double* dl = dfr + 3 * pair_dindex(mi, ja, q, 0);
+    const double del[2] = {ld_uniform(dl), ld_uniform(dl + 1)};
     bool cj;
     const cx<R>* src = pairsrc(q, cj);
     const double dsg = cj ? -1.0 : 1.0;   // shift of the loaded pair relative to (q, ja)
