@@ -1204,9 +1204,10 @@ struct EngineT : Engine {
       return 0;
     };
     if (!pb.pair_store || P == 0) return none();
-    if (P != cap_P_) {   // the cap counts columns of one problem size
+    const int key = (P * 2 + int(pb.bitc)) * 2 + pb.nspin - 1;
+    if (key != cap_key_) {   // the cap counts columns of one problem shape
       store_cap_ = INT_MAX;
-      cap_P_ = P;
+      cap_key_ = key;
     }
     // elements of the store with Q1 partner columns: triangular rows in TC mode, P x Q1 in the biorthogonal one
     const size_t per_pair = size_t(5) * pb.nspin * NR;
@@ -1248,8 +1249,8 @@ struct EngineT : Engine {
     }
     return 0;
   }
-  int store_cap_ = INT_MAX;   // most partner columns an allocation may still ask for (at P = cap_P_)
-  int cap_P_ = -1;
+  int store_cap_ = INT_MAX;   // most partner columns an allocation may still ask for (at the shape cap_key_)
+  int cap_key_ = -1;
 
   // Bytes of per-batch pair buffers.  Without a caller budget: an eighth of the device's memory, between
   // 8 and 32 GiB (32 GiB on a 288 GB device: 134 targets per batch at 256 orbitals and 24^3 in FP32);
