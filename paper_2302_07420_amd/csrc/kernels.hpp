@@ -988,7 +988,7 @@ __device__ __forceinline__ void inv48_pair(cx<R>* v, R hf) {
 
 // The z stage of k_zconv at N = 48 with each column on a lane pair (same operations, inputs and outputs).
 template <typename R, int OP>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 3 : 2)))
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 && OP != OP_A2 ? 3 : 2)))
 k_zconv48(const cx<R>* in, cx<R>* out, long npairs, int t0, MeshInfo mi, Tables tb, int sign_target_minus_partner,
           const cx<R>* inB = nullptr) {
   constexpr int N = 48, H = 24, NN = N * N;
@@ -1049,6 +1049,50 @@ k_zconv48(const cx<R>* in, cx<R>* out, long npairs, int t0, MeshInfo mi, Tables 
       __builtin_amdgcn_sched_barrier(0);
       o += 2 * NR;
     }
+  } else if constexpr (OP == OP_A2 && sizeof(R) == 4) {
+    // software pipeline (FP32 at 2 waves per SIMD): the next input is requested before this one is
+    // transformed; input k is channel k / 2, its P (even k) or R (odd k) field
+    cx<R> acc[H], v[H], nx[H];
+#pragma unroll
+    for (int j = 0; j < H; ++j) acc[j] = mk<R>(R(0), R(0));
+    const int nin = 2 * (NIN / 2 + (inB ? 1 : 0));
+    auto src = [&](int k) -> const cx<R>* {
+      const int s = k >> 1;
+      return (s == NIN / 2 ? inB + pair * 2 * NR : in + (pair * NIN + 2 * s) * NR) + (k & 1) * NR + xy + zo;
+    };
+    {
+      const cx<R>* b = src(0);
+#pragma unroll
+      for (int j = 0; j < H; ++j) v[j] = b[j * NN];
+    }
+#pragma unroll 1
+    for (int k = 0; k < nin; ++k) {
+      if (k + 1 < nin) {
+        const cx<R>* b = src(k + 1);
+#pragma unroll
+        for (int j = 0; j < H; ++j) nx[j] = b[j * NN];
+      }
+      fwd48_pair(v, hf);
+      const int s = k >> 1;
+      const bool isB = s == NIN / 2;
+      const R* tu = (s == 1 && !isB) ? tU1 : tU0;
+      const R sg = isB ? R(-1) : R(1);
+      if (k & 1) {
+#pragma unroll
+        for (int j = 0; j < H; ++j) acc[j] = acc[j] + (kap3(j) * (sg * tu[2 * j * NN])) * v[j];
+      } else {
+#pragma unroll
+        for (int j = 0; j < H; ++j) acc[j] = acc[j] + (sg * tu[2 * j * NN]) * v[j];
+      }
+#pragma unroll
+      for (int j = 0; j < H; ++j) v[j] = nx[j];
+    }
+#pragma unroll
+    for (int j = 0; j < H; ++j) acc[j] = mul_i(R(-1) * acc[j]);
+    inv48_pair(acc, hf);
+    cx<R>* o = out + pair * NR + xy + zo;
+#pragma unroll
+    for (int j = 0; j < H; ++j) o[j * NN] = acc[j];
   } else {
     cx<R> acc[H], v[H];
 #pragma unroll
