@@ -357,7 +357,7 @@ __host__ __device__ __forceinline__ long tri_row(int t, int Q1) {
 // Pair p of a z-stage launch -> its row t of the batch and partner q.  Rectangular batches have rows of mi.P
 // pairs.  A triangular one (mi.trq > 0) is the rows t0 + t of the triangular store with Q1 = trq, of
 // min(t0 + t + 1, trq) pairs each, one after another; its input rows (the batch's pair planes) hold mi.P.
-__device__ __forceinline__ void pair_tq(const MeshInfo& mi, int t0, long p, int& t, int& q) {
+__host__ __device__ __forceinline__ void pair_tq(const MeshInfo& mi, int t0, long p, int& t, int& q) {
   if (mi.trq <= 0) {
     t = int(p / mi.P);
     q = int(p - long(t) * mi.P);

@@ -12,6 +12,8 @@
 //   jk <Q2> <A> <C> <u> <lap u> <(grad u)^2>   Jastrow kernels at |Q|^2 (Sec. 2.6.3, App. B)
 //   tangent <dir> <exact> <central difference> derivative of the kernels along one parameter
 //   sym <nirr> <orbit sizes...>                 representative k-points of the mesh under the operations
+//   tri <pairs> <mismatches>                   triangular pair store: row offsets and the z stage's decode
+//                                              of a batch's pairs, against plain enumeration
 //   FAIL <line> <condition>                    an internal check that did not hold
 // Input (argv[1], whitespace separated): lattice rows (9); k-mesh (3); A (2); C (2); alpha; ecut;
 // nsym and nsym x (R row-major, 9 integers; tau, 3 fractions); nq and nq values of |Q|^2;
@@ -204,6 +206,32 @@ int main(int argc, char** argv) {
   if (nkb > 0) {
     code("band", tc_set_band_kpoints(c, nkb, kb.data()));
     code("band_basis_index", tc_set_band_basis(c, nkb, 1, m_dup));
+  }
+  // the triangular store of TC mode: row offsets (rows of min(t + 1, Q1) pairs) and the decode of pair p of
+  // a target batch into its row and partner, against enumerating the rows
+  {
+    const int cases[][3] = {{8, 2, 3},     {12, 4, 6},     {12, 12, 12},  {256, 16, 256},
+                            {256, 16, 208}, {256, 134, 256}, {1000, 37, 700}, {4096, 64, 4096}};
+    long n = 0, bad = 0;
+    for (const auto& cs : cases) {
+      const int P = cs[0], T = cs[1], Q1 = cs[2];
+      bad += tcmi::tri_row(P, P) != long(P) * (P + 1) / 2;
+      for (int t0 = 0; t0 < P; t0 += T) {
+        const int nt = std::min(T, P - t0);
+        tcmi::MeshInfo mi{};
+        mi.P = std::min(t0 + nt, Q1);
+        mi.trq = Q1;
+        long p = 0;
+        for (int t = 0; t < nt; ++t)
+          for (int q = 0; q < std::min(t0 + t + 1, Q1); ++q, ++p, ++n) {
+            int tt = -1, qq = -1;
+            tcmi::pair_tq(mi, t0, p, tt, qq);
+            bad += tt != t || qq != q;
+          }
+        bad += p != tcmi::tri_row(t0 + nt, Q1) - tcmi::tri_row(t0, Q1);
+      }
+    }
+    std::printf("tri %ld %ld\n", n, bad);
   }
   std::printf("done %d\n", g_fail);
   return g_fail == 0 ? 0 : 1;

@@ -10,7 +10,8 @@ documented errors, and compares the host tables with the oracle and with closed 
     including the small-g series branch;
   * the exact tangents of the kernels along A and C (dual numbers) with central differences;
   * the orbits of the 2x2x2 Gamma-centred mesh of the fcc lattice under O_h: Gamma, the four L-type
-    and the three X-type points (3 representatives, orbit sizes 1, 3, 4).
+    and the three X-type points (3 representatives, orbit sizes 1, 3, 4);
+  * the triangular pair store's row offsets and the z stage's decode of a pair into row and partner.
 """
 import os
 import subprocess
@@ -116,6 +117,14 @@ def test_kernel_tangents_equal_central_differences(run):
     assert len(rows) == 8
     for exact, fd in rows:
         assert exact == pytest.approx(fd, rel=1e-6, abs=1e-9)
+
+
+def test_triangular_pair_store_rows_and_decode(run):
+    """The triangular store's rows and the z stage's decode of a batch's pair index into (row, partner)
+    agree with enumerating the rows, for whole and partial stores and batches that do not divide P."""
+    _, _, r = run
+    n, bad = (int(x) for x in next(ln for ln in r.stdout.splitlines() if ln.startswith("tri ")).split()[1:])
+    assert n > 8_000_000 and bad == 0
 
 
 def test_fcc_mesh_orbits_under_the_diamond_group(run):
