@@ -518,7 +518,8 @@ __device__ __forceinline__ void comb_pass48(cx<R>* sm, int np, int tid, int nth)
 // 16-point comb (32 registers in FP32) instead of a 48-point line.  Ends with a barrier.
 // BAL: the row and column passes take one (line, comb) per task (comb_pass48); otherwise a thread takes a
 // whole line's three combs in turn (fewer threads busy, a shorter instruction stream), which measured
-// faster in k_fused_A and slower in k_fused_O and k_passB_xy.
+// faster in k_fused_A's inverse transforms and slower everywhere else (k_fused_A's forward transforms,
+// k_fused_O, k_passB_xy).
 template <typename R, int DIR, bool BAL>
 __device__ __forceinline__ void planes_comb48(cx<R>* sm, int np, int tid, int nth) {
   constexpr int N = 48, LD = N + 1, PL = N * LD;
@@ -1547,7 +1548,7 @@ k_fused_A(const cx<R>* buf5, const cx<R>* psi, const cx<R>* Dl, const cx<R>* Hl,
       if (do3b6) {
         // forward xy of the T planes (slots 1..6 unsplit; 1..3 or 0..2 split), then the split form
         const int s0 = (SPLIT && g == 1) ? 0 : 1;
-        planes_fft<R, N, -1>(sm + s0 * PL, SPLIT ? 3 : 6, threadIdx.x);
+        planes_fft<R, N, -1, true>(sm + s0 * PL, SPLIT ? 3 : 6, threadIdx.x);
         cx<R>* dst = src4 + pair * 4 * NR;
 #pragma unroll
         for (int i = 0; i < KP; ++i) {
