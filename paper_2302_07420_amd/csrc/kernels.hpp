@@ -516,10 +516,10 @@ __device__ __forceinline__ void comb_pass48(cx<R>* sm, int np, int tid, int nth)
 // Chinese-remainder map k = 16 k1 + 33 k2, so output k sits at sigma48(k) on each axis; with the input
 // at sigma48 positions the output is in natural order (the two maps swap roles).  A thread holds one
 // 16-point comb (32 registers in FP32) instead of a 48-point line.  Ends with a barrier.
-// BAL: the row and column passes take one (line, comb) per task (comb_pass48); otherwise a thread takes a
-// whole line's three combs in turn (fewer threads busy, a shorter instruction stream), which measured
-// faster in k_fused_A's inverse transforms and slower everywhere else (k_fused_A's forward transforms,
-// k_fused_O, k_passB_xy).
+// BAL: the row and column passes take one (line, comb) per task (comb_pass48); otherwise the row pass gives
+// a thread a whole row's three combs in turn (fewer threads busy, a shorter instruction stream) and the
+// column pass takes one (column, comb) per task, which measured faster in k_fused_A's inverse transforms
+// and slower everywhere else (k_fused_A's forward transforms, k_fused_O, k_passB_xy, k_fused_Y, k_pair_xy).
 template <typename R, int DIR, bool BAL>
 __device__ __forceinline__ void planes_comb48(cx<R>* sm, int np, int tid, int nth) {
   constexpr int N = 48, LD = N + 1, PL = N * LD;
@@ -537,16 +537,7 @@ __device__ __forceinline__ void planes_comb48(cx<R>* sm, int np, int tid, int nt
       comb16<R, DIR, 2, 1>(row);
     }
     __syncthreads();
-    for (int t = tid; t < np * N; t += nth) {
-      const int p = t / N, x = t - p * N;
-      cx<R>* col = sm + p * PL + x;
-      comb16<R, DIR, 0, LD>(col);
-      __builtin_amdgcn_sched_barrier(0);
-      comb16<R, DIR, 1, LD>(col);
-      __builtin_amdgcn_sched_barrier(0);
-      comb16<R, DIR, 2, LD>(col);
-    }
-    __syncthreads();
+    comb_pass48<R, DIR, true>(sm, np, tid, nth);
   }
   for (int t = tid; t < np * 256; t += nth) {
     const int p = t >> 8, ky = (t >> 4) & 15, kx = t & 15;
