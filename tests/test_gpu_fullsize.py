@@ -14,7 +14,8 @@ checks what it can compute independently:
     oracle takes about 15 s): every term alone and all terms together, element by
     element, in FP64, FP32 and split BF16, with the pair store on and off and with
     batches whose last one is partial;
-  * a small problem on the 48^3 grid: all terms, element by element, in FP64 and FP32.
+  * a small problem on the 48^3 grid: all terms, element by element, in FP64 and FP32, in TC mode,
+    the biorthogonal mode, spin-polarised, and both.
 """
 import numpy as np
 import pytest
@@ -217,6 +218,49 @@ def test_grid_48_all_terms(prec, tol):
             e = max(np.abs(a - b).max() for a, b in zip(hc, per[t])) / scale
             _say(f"    term {t}: {e:.3e}")
             assert e < FP64_TOL, (t, e)
+
+
+_GRID48_REF = {}   # oracle outputs per mode, shared by the precisions
+
+
+def _grid48_workload(mode):
+    """A small problem on the 48^3 grid in the biorthogonal mode, spin-polarised, or both."""
+    left = 0.15 if "bitc" in mode else None
+    w = T.tiny_fcc(kmesh=(2, 1, 1), grid=48, ecut=3.0, nb=2, a=7.0, occ=[1.0, 0.7], left_mix=left,
+                   seed_offset=3)
+    if "pol" in mode:
+        w = T.polarized(w, 41, occ_dn=[0.9, 0.2])
+    return w
+
+
+@pytest.mark.parametrize("mode,prec,tol", [(m, p, t) for m in ("bitc", "pol", "bitc_pol")
+                                           for p, t in (("fp64", FP64_TOL), ("fp32", FP32_TOL))])
+def test_grid_48_all_terms_other_modes(mode, prec, tol):
+    """48-point plane kernels of the biorthogonal occupied pass (k_fused_OB), the spin-polarised pass A and
+    occupied pass (k_fused_A<POL>, k_fused_O<SPLITH>) and their FP64 separate-round layouts, against the
+    oracle: every output element of every spin channel, and the energy."""
+    chans = (0, 1) if "pol" in mode else (0,)
+    if mode not in _GRID48_REF:
+        w = _grid48_workload(mode)
+        _say(f"[oracle] tiny fcc 48^3 {mode}: all terms (FP64 CPU)")
+        pr = Problem(w)
+        tot = {s: [c.numpy() for c in pr.to_coeff(sum(MULT.get(t, 1) * pr.term(t, s) for t in ALL), s)]
+               for s in chans}
+        _GRID48_REF[mode] = (w, tot, float(pr.energy()))
+    w, tot, E = _GRID48_REF[mode]
+    _say(f"[gpu] tiny fcc 48^3 {mode} {prec}: all terms vs oracle")
+    op = tc.from_workload(w, precision=tc.TC_PREC_FP64 if prec == "fp64" else tc.TC_PREC_FP32)
+    hc = op.apply()
+    Eg, _ = op.energy()
+    op.close()
+    for s in chans:
+        got = hc[s] if "pol" in mode else hc
+        scale = max(np.abs(x).max() for x in tot[s])
+        err = max(np.abs(a - b).max() for a, b in zip(got, tot[s])) / scale
+        _say(f"    spin {s}: max element error / max |h c| = {err:.3e}")
+        assert err < tol, (s, err)
+    _say(f"    energy {Eg!r} vs oracle {E!r} (rel {abs(Eg - E) / abs(E):.3e})")
+    assert abs(Eg - E) < (FP64_TOL if prec == "fp64" else 1e-6) * abs(E)
 
 
 @pytest.fixture(scope="module")
