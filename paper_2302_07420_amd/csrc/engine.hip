@@ -1404,6 +1404,11 @@ struct EngineT : Engine {
     const int Q1 = (!ts && !sym && need_occ && need_A) ? pair_store(pb) : 0;   // stored partner columns
     const bool keepA = Q1 > 0;
     const bool tri = keepA && !pb.bitc;   // TC mode: the triangular store (tri_row)
+    // TC mode, one channel, with the store: h5 of Alg. 3a2 comes from pass A (k_fused_A<H5A>), whose targets are
+    // the occupied pass's rows and whose pair fields are the conjugates of the occupied pass's, so the occupied
+    // pass transforms the parallel channel only (H3a4).  h6 is then complete after the last target batch, and
+    // its local term is applied to every target after the batches (k_h6_sum, k_h6_apply, k_h6_energy).
+    const bool h5A = tri && !pol && m.m3a2 != 0;
     ensure(pb, pair_budget(pb));
     // targets: the orbitals, or nbt trial vectors per k-point
     const int nbt = ts ? ts->nvec : nb;
@@ -1704,10 +1709,13 @@ struct EngineT : Engine {
                 zconv<OP_O>(s, npair, a0, mi, tb, 0);
               });
             }
-            K(TC_K_FUSED_O, fb * (4.0 * npair + P) + (pol ? 4.5 : 3.5) * fb * nt * S, [&] {
+            K(TC_K_FUSED_O, fb * ((h5A ? 2.0 : 4.0) * npair + P) + (pol ? 4.5 : 3.5) * fb * nt * S, [&] {
               if (pol)
                 hipLaunchKernelGGL((k_fused_O<R, N, true>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, b4, PSI[c],
                                    W[c], fa, mi, rc, dfr.p, h5part.p, H3part.p, sT, sQ, trs, Q1);
+              else if (h5A)
+                hipLaunchKernelGGL((k_fused_O<R, N, false, false>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, b4,
+                                   PSI[c], W[c], fa, mi, rc, dfr.p, h5part.p, H3part.p, sT, sQ, trs, Q1);
               else
                 hipLaunchKernelGGL((k_fused_O<R, N>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, b4, PSI[c], W[c],
                                    fa, mi, rc, dfr.p, h5part.p, H3part.p, sT, sQ, trs, Q1);
@@ -1813,6 +1821,8 @@ struct EngineT : Engine {
         const long npair = long(nt) * P;
         TC_HIP(hipMemsetAsync(acc.p, 0, size_t(kAccSlots) * T * NR * sizeof(cx<double>), s));
         TC_HIP(hipMemsetAsync(h4.p, 0, size_t(3) * T * NR * sizeof(cx<R>), s));
+        // h4 of the batch's targets (Alg. 3a3): from pass A, or on the h5A path the occupied pass's H3a4 rows
+        const cx<R>* h4b = h5A ? H3[c] + size_t(t0) * 3 * NR : h4.p;
         if (!t_arena)
           for (int i = 0; i < 3; ++i) {
             hipEvent_t e;
@@ -1846,7 +1856,7 @@ struct EngineT : Engine {
           // POL: the antiparallel 3b6 sources take the other channel's density; CN: complex densities
           const cx<R>* nA = pol ? NJ[o] : nullptr;
           const int do3b6 = int(m.m3b6 != 0);
-          K(TC_K_FUSED_A, fb * ((m.m3b6 ? 9.0 : 5.0) * npair + 8.0 * P + nt) + 6.0 * part, [&] {
+          K(TC_K_FUSED_A, fb * ((m.m3b6 ? 9.0 : 5.0) * npair + 8.0 * P + nt) + (h5A ? 3.5 : 6.0) * part, [&] {
             const dim3 g(unsigned(nt) * N * S), b(NTH);
             if (pol && bitc)
               hipLaunchKernelGGL((k_fused_A<R, N, true, true>), g, b, 0, s, bufB.p, PSI[c], DL[c], HL[c], NJ[c], W[c], fa,
@@ -1857,13 +1867,22 @@ struct EngineT : Engine {
             else if (bitc)
               hipLaunchKernelGGL((k_fused_A<R, N, false, true>), g, b, 0, s, bufB.p, PSI[c], DL[c], HL[c], NJ[c], W[c], fa,
                                  m, do3b6, miT, bm, mm, dfr.p, bufA.p, gpart.p, h4part.p, nA, stp, Q1, int(tri), int(formA));
+            else if (h5A)
+              hipLaunchKernelGGL((k_fused_A<R, N, false, false, true>), g, b, 0, s, bufB.p, PSI[c], DL[c], HL[c], NJ[c],
+                                 W[c], fa, m, do3b6, miT, bm, mm, dfr.p, bufA.p, gpart.p, h4part.p, nA, stp, Q1, int(tri),
+                                 int(formA), h5part.p);
             else
               hipLaunchKernelGGL((k_fused_A<R, N, false, false>), g, b, 0, s, bufB.p, PSI[c], DL[c], HL[c], NJ[c], W[c],
                                  fa, m, do3b6, miT, bm, mm, dfr.p, bufA.p, gpart.p, h4part.p, nA, stp, Q1, int(tri), int(formA));
           });
+          if (h5A)
+            K(TC_K_SUM_PARTS, 0.5 * fb * nt * (S + 1), [&] {
+              hipLaunchKernelGGL((k_sum_real_parts<R, N>), dim3(nblk(long(nt) * NR)), dim3(256), 0, s, S, nt, t0,
+                                 h5part.p, H5P[c]);
+            });
           K(TC_K_SUM_PARTS, 6.0 * part + 6.0 * fd * nt + 3.0 * fb * nt, [&] {
             hipLaunchKernelGGL((k_sum_parts<R, N>), dim3(nblk(long(nt) * NR)), dim3(256), 0, s, 1, S, nt, t0, 0,
-                               nullptr, nullptr, gpart.p, h4part.p, nullptr, nullptr, acc.p, h4.p);
+                               nullptr, nullptr, gpart.p, h5A ? nullptr : h4part.p, nullptr, nullptr, acc.p, h4.p);
           });
           if (ts && ts->bdh4) {   // band k-points: h4 of Alg. 3a3 (h3 of Alg. 3b4) corrected at q1 -> k, then <psi_mu|h4_j>
             hipLaunchKernelGGL((k_band_dh4<R, N>), dim3(nblk(long(nt) * NR)), dim3(256), 0, s, tP, ts->bdh4, ts->bV,
@@ -1897,7 +1916,7 @@ struct EngineT : Engine {
           cx<R>* zout = merged ? bufB.p + size_t(2) * npair * NR : bufB.p;
           K(TC_K_OTHER, fb * 13.0 * nt, [&] {
             hipLaunchKernelGGL((k_passB_Z<R, N>), dim3(nblk(long(nt) * NR)), dim3(256), 0, s, tP, tD, LOC[c] + NR,
-                               h4.p, t0, nt, NTG, m, bm, Z.p);
+                               h4b, t0, nt, NTG, m, bm, Z.p);
           });
           K(TC_K_XY_PASSB, fb * (2.0 * npair + 4.0 * P + 4.0 * nt), [&] {
             hipLaunchKernelGGL((k_passB_xy<R, N>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, tP, XS[c], Z.p,
@@ -1923,7 +1942,7 @@ struct EngineT : Engine {
         }
         if (be) TC_HIP(hipEventRecord(be[2], s));
         K(TC_K_OTHER, fb * 16.0 * nt + 8.0 * fd * nt, [&] {
-          hipLaunchKernelGGL((k_local<R, N>), dim3(nblk(long(nt) * NR)), dim3(256), 0, s, tP, tD, LOC[c], h4.p, t0, nt,
+          hipLaunchKernelGGL((k_local<R, N>), dim3(nblk(long(nt) * NR)), dim3(256), 0, s, tP, tD, LOC[c], h4b, t0, nt,
                              NTG, m, acc.p, g.p);
           if (!ts)
             hipLaunchKernelGGL((k_epart<R, N>), dim3(kAccSlots * nt), dim3(256), 0, s, sym ? psiT.p : XS[c], acc.p, t0,
@@ -1935,6 +1954,26 @@ struct EngineT : Engine {
                              t0, nt, 1.0 / double(NR),
                              (ts ? ts->out + c * tcofs : sym ? sh.outI.p : sh.out.p + c * cofs), NR,
                              sym ? sh.irrk.p : nullptr);
+        });
+      }
+    }
+    if (h5A) {   // the local 3a2 term with h6 from pass A: h6 psi_j, r -> G, added to each target's output
+      cx<R>* h6 = LOC[0] + 6 * NR;
+      K(TC_K_OTHER, fb * 0.5 * P + fb, [&] {
+        hipLaunchKernelGGL((k_h6_sum<R, N>), dim3(nblk(NR)), dim3(256), 0, s, H5P[0], W[0], P, h6);
+      });
+      for (int t0 = 0; t0 < NTG; t0 += T) {
+        const int nt = std::min(T, NTG - t0);
+        K(TC_K_OTHER, fb * (2.0 * nt + 1.0), [&] {
+          hipLaunchKernelGGL((k_h6_apply<R, N>), dim3(nblk(long(nt) * NR)), dim3(256), 0, s, PSI[0], h6, t0, nt,
+                             R(0.5 * m.m3a2), g.p);
+          hipLaunchKernelGGL((k_h6_energy<R, N>), dim3(nt), dim3(256), 0, s, XS[0], h6, t0, 0.5 * m.m3a2, 2,
+                             sh.epart.p);
+        });
+        fft3d_t<R, N>(g.p, nt, -1, s, pf);
+        K(TC_K_OTHER, 0.0, [&] {
+          hipLaunchKernelGGL((k_gather<R>), dim3(nblk(long(nt) * tnpm)), dim3(256), 0, s, g.p, tbox, tnpw, nbt, tnpm,
+                             t0, nt, 1.0 / double(NR), sh.out.p, NR, nullptr, 1);
         });
       }
     }

@@ -146,7 +146,7 @@ __global__ void k_scatter(const double* coef, const int* boxidx, const int* npw,
 // r -> G of per-target fields: out[j][g] (complex128) = field_j(box(g)) * scale, zero beyond npw
 template <typename R>
 __global__ void k_gather(const cx<R>* f, const int* boxidx, const int* npw, int nb, int npw_max, int j0, int nt,
-                         double scale, double* out, long nr, const int* kmap = nullptr) {
+                         double scale, double* out, long nr, const int* kmap = nullptr, int add = 0) {
   const long t = long(blockIdx.x) * blockDim.x + threadIdx.x;
   if (t >= long(nt) * npw_max) return;
   const int jt = int(t / npw_max), g = int(t - long(jt) * npw_max);
@@ -157,6 +157,10 @@ __global__ void k_gather(const cx<R>* f, const int* boxidx, const int* npw, int 
     const cx<R> v = f[long(jt) * nr + boxidx[long(ik) * npw_max + g]];
     re = double(v.x) * scale;
     im = double(v.y) * scale;
+  }
+  if (add) {   // accumulate onto what an earlier gather wrote
+    re += out[2 * (long(j) * npw_max + g)];
+    im += out[2 * (long(j) * npw_max + g) + 1];
   }
   out[2 * (long(j) * npw_max + g)] = re;
   out[2 * (long(j) * npw_max + g) + 1] = im;
@@ -1376,12 +1380,16 @@ constexpr int kFusedAWaves = (sizeof(R) == 4 && N == 24) ? 3 : 1;
 // POL (spin-polarised runs): the antiparallel-channel 3b6 sources take the other spin's density nA.
 // CN: the density is complex (biorthogonal mode, n = sum w conj(chi) psi); otherwise only its real part is
 // read (n = sum w |psi|^2).
-template <typename R, int N, bool POL = false, bool CN = true>
+// H5A (TC mode, the orbitals as targets, pair store): h5[t] += w_q (|V_par|^2 + |V_anti|^2) (Alg. 3a2) into
+// h5part ([S][T][N^3], real) in place of h4.  The occupied pass's V of the pair (a = t, b = q) is the conjugate
+// of this pair's real-space fields (its density is the conjugate, its shift the negative), so the norms are
+// the same, and its H3a4[t] = sum_q w_q conj(V_par) psi_q equals h4[t], which the caller takes from there.
+template <typename R, int N, bool POL = false, bool CN = true, bool H5A = false>
 __global__ void __launch_bounds__((Fz<R, N>::NTH)) __attribute__((amdgpu_waves_per_eu(kFusedAWaves<R, N>)))
 k_fused_A(const cx<R>* buf5, const cx<R>* psi, const cx<R>* Dl, const cx<R>* Hl, const cx<R>* n, const double* w,
           FusedArgs fa, Masks m, int do3b6, MeshInfo mi, Basis<R> B, Basis<R> M, const double* dfr, cx<R>* src4,
           cx<R>* gpart, cx<R>* h4part, const cx<R>* nA = nullptr, const cx<R>* store = nullptr, int Q1 = 0,
-          int tri = 0, int formed = 1) {
+          int tri = 0, int formed = 1, R* h5part = nullptr) {
   using F = Fz<R, N>;
   constexpr int KP = F::KP, RB = F::RB, PL = F::PLANE;
   constexpr bool SPLIT = PassA<R, N>::SPLIT;
@@ -1391,6 +1399,15 @@ k_fused_A(const cx<R>* buf5, const cx<R>* psi, const cx<R>* Dl, const cx<R>* Hl,
   const PlaneWG<R, N> wg(fa);
   const int jt = fa.t0 + wg.t;
   cx<R> ga[KP][3], h4[KP][3], nk[KP], na[POL ? KP : 1];
+  R h5k[H5A ? KP : 1];
+  // |X|^2 of a Cartesian vector from its lattice components Y: Y^H M Y with the metric M = B B^T
+  auto norm2 = [&](const cx<R>* Y) {
+    R v = M.b[0] * (Y[0].x * Y[0].x + Y[0].y * Y[0].y) + M.b[4] * (Y[1].x * Y[1].x + Y[1].y * Y[1].y) +
+          M.b[8] * (Y[2].x * Y[2].x + Y[2].y * Y[2].y);
+    v += R(2) * (M.b[1] * (Y[0].x * Y[1].x + Y[0].y * Y[1].y) + M.b[2] * (Y[0].x * Y[2].x + Y[0].y * Y[2].y) +
+                 M.b[5] * (Y[1].x * Y[2].x + Y[1].y * Y[2].y));
+    return v;
+  };
   unsigned ob[KP];   // byte offsets of the owned points within a volume
 #pragma unroll
   for (int i = 0; i < KP; ++i) ob[i] = (wg.zo + RB * N * i) * unsigned(sizeof(cx<R>));
@@ -1398,6 +1415,7 @@ k_fused_A(const cx<R>* buf5, const cx<R>* psi, const cx<R>* Dl, const cx<R>* Hl,
   for (int i = 0; i < KP; ++i) {
 #pragma unroll
     for (int s = 0; s < 3; ++s) ga[i][s] = h4[i][s] = mk<R>(R(0), R(0));
+    if constexpr (H5A) h5k[i] = R(0);
     nk[i] = ldo(n, ob[i]);
     if constexpr (POL) na[i] = ldo(nA, ob[i]);
   }
@@ -1508,23 +1526,30 @@ k_fused_A(const cx<R>* buf5, const cx<R>* psi, const cx<R>* Dl, const cx<R>* Hl,
           }
           ga[i][1] = ga[i][1] + (a1 * wq) * sD;
           ga[i][2] = ga[i][2] + (a2 * wq) * sH;
+          if constexpr (H5A) {
+            h5k[i] += wq * norm2(Y);
+          } else {
 #pragma unroll
-          for (int d = 0; d < 3; ++d) cfma(h4[i][d], wq, Y[d], p);
+            for (int d = 0; d < 3; ++d) cfma(h4[i][d], wq, Y[d], p);
+          }
           if (do3b6) {
 #pragma unroll
             for (int d = 0; d < 3; ++d) sm[(1 + d) * PL + so] = CN ? Y[d] * nk[i] : nk[i].x * Y[d];
           }
         }
-        if (anti && do3b6) {
+        if (anti && (do3b6 || H5A)) {
           cx<R> nanti;
           if constexpr (POL)
             nanti = na[i];
           else
             nanti = nk[i];
+          cx<R> y[3];
 #pragma unroll
-          for (int d = 0; d < 3; ++d) {
-            const cx<R> y = rd((ab + d) * PL + so);
-            sm[(ab + d) * PL + so] = CN ? y * nanti : nanti.x * y;
+          for (int d = 0; d < 3; ++d) y[d] = rd((ab + d) * PL + so);
+          if constexpr (H5A) h5k[i] += wq * norm2(y);
+          if (do3b6) {
+#pragma unroll
+            for (int d = 0; d < 3; ++d) sm[(ab + d) * PL + so] = CN ? y[d] * nanti : nanti.x * y[d];
           }
         }
       }
@@ -1533,8 +1558,14 @@ k_fused_A(const cx<R>* buf5, const cx<R>* psi, const cx<R>* Dl, const cx<R>* Hl,
 #pragma unroll
       for (int i = 0; i < KP; ++i)
 #pragma unroll
-        for (int s = 0; s < 3; ++s)
-          asm volatile("" : "+v"(ga[i][s].x), "+v"(ga[i][s].y), "+v"(h4[i][s].x), "+v"(h4[i][s].y));
+        for (int s = 0; s < 3; ++s) {
+          if constexpr (H5A)
+            asm volatile("" : "+v"(ga[i][s].x), "+v"(ga[i][s].y));
+          else
+            asm volatile("" : "+v"(ga[i][s].x), "+v"(ga[i][s].y), "+v"(h4[i][s].x), "+v"(h4[i][s].y));
+        }
+#pragma unroll
+      for (int i = 0; i < (H5A ? KP : 0); ++i) asm volatile("" : "+v"(h5k[i]));
       __syncthreads();
       if (do3b6) {
         // forward xy of the T planes (slots 1..6 unsplit; 1..3 or 0..2 split), then the split form
@@ -1569,8 +1600,9 @@ k_fused_A(const cx<R>* buf5, const cx<R>* psi, const cx<R>* Dl, const cx<R>* Hl,
 #pragma unroll
     for (int s = 0; s < 3; ++s) {
       sto(gp + s * NR, ob[i], ga[i][s]);
-      sto(hp + s * NR, ob[i], hc[s]);
+      if constexpr (!H5A) sto(hp + s * NR, ob[i], hc[s]);
     }
+    if constexpr (H5A) sto(h5part + (long(wg.c) * fa.T + wg.t) * NR, ob[i] / unsigned(sizeof(cx<R>) / sizeof(R)), h5k[i]);
   }
 }
 
@@ -1623,18 +1655,21 @@ struct PassO {
 // SPLITH (spin-polarised runs): the parallel- and antiparallel-channel parts of h5 are kept apart, the
 // antiparallel one in the second half of h5part ([2][S][T][N^3]); they serve targets of the partners' own
 // spin and of the other spin respectively.
-template <typename R, int N, bool SPLITH = false>
+// H5 = false: only H3a4, from the parallel channel's three planes (h5part is written as zeros); in TC mode
+// with the pair store, pass A accumulates h5 of every target from the same fields (k_fused_A<H5A>).
+template <typename R, int N, bool SPLITH = false, bool H5 = true>
 __global__ void __launch_bounds__((Fz<R, N>::NTH)) k_fused_O(const cx<R>* buf4, const cx<R>* psi, const double* w,
                                                            FusedArgs fa, MeshInfo mi, Recip rc, const double* dfr,
                                                            R* h5part, cx<R>* H3part, long sT = -1, long sQ = 4,
                                                            const cx<R>* trs = nullptr, int Q1 = 0) {
   using F = Fz<R, N>;
   constexpr int KP = F::KP, RB = F::RB, PL = F::PLANE;
-  constexpr bool SPLIT = PassO<R, N>::SPLIT;
+  constexpr bool SPLIT = H5 && PassO<R, N>::SPLIT;
   constexpr bool PF = !SPLIT && F::PREFETCH;
+  constexpr int NF = H5 ? 4 : 2;   // pair fields read: W0, W3 of the parallel channel (and the antiparallel)
   if (sT < 0) sT = 4L * fa.P;
   constexpr long NR = long(N) * N * N;
-  __shared__ cx<R> sm[PassO<R, N>::NPL * PL];
+  __shared__ cx<R> sm[(H5 ? PassO<R, N>::NPL : 3) * PL];
   const PlaneWG<R, N> wg(fa);
   const Basis<R> B = basis<R>(rc);
   // |X|^2 of a Cartesian vector X_c = sum_d B_dc Y_d from its lattice components: Y^H M Y with the metric
@@ -1674,12 +1709,12 @@ __global__ void __launch_bounds__((Fz<R, N>::NTH)) k_fused_O(const cx<R>* buf4, 
   };
   auto ld = [&](const cx<R>* src, int f, int i) -> cx<R> { return src[f * NR + wg.zo + RB * N * i]; };
   // the next partner's four pair planes are loaded into registers while this partner is transformed
-  cx<R> pre[4][KP];
+  cx<R> pre[NF][KP];
   auto fetch = [&](int q) {
     bool cj;
     const gptr<cx<R>> src = uniform_global(pairsrc(q, cj));
 #pragma unroll
-    for (int f = 0; f < 4; ++f)
+    for (int f = 0; f < NF; ++f)
 #pragma unroll
       for (int i = 0; i < KP; ++i) pre[f][i] = ldo(src + f * NR, (wg.zo + RB * N * i) * unsigned(sizeof(cx<R>)));
   };
@@ -1694,7 +1729,7 @@ __global__ void __launch_bounds__((Fz<R, N>::NTH)) k_fused_O(const cx<R>* buf4, 
     const R k1 = R(double(mfreq<N>(wg.x)) + dsg * del[0]);
 #pragma unroll 1
     for (int g = 0; g < (SPLIT ? 2 : 1); ++g) {
-      const bool par = !SPLIT || g == 0, anti = !SPLIT || g == 1;
+      const bool par = !SPLIT || g == 0, anti = H5 && (!SPLIT || g == 1);
       const int ab = SPLIT ? 0 : 3;
 #pragma unroll
       for (int i = 0; i < KP; ++i) {
@@ -1706,16 +1741,18 @@ __global__ void __launch_bounds__((Fz<R, N>::NTH)) k_fused_O(const cx<R>* buf4, 
           sm[PL + so] = mul_i(k2 * w0);
           sm[2 * PL + so] = !PF ? ld(src, 1, i) : pre[1][i];
         }
-        if (anti) {
-          const cx<R> w0 = !PF ? ld(src, 2, i) : pre[2][i];
-          sm[ab * PL + so] = mul_i(k1 * w0);
-          sm[(ab + 1) * PL + so] = mul_i(k2 * w0);
-          sm[(ab + 2) * PL + so] = !PF ? ld(src, 3, i) : pre[3][i];
+        if constexpr (H5) {
+          if (anti) {
+            const cx<R> w0 = !PF ? ld(src, 2, i) : pre[2][i];
+            sm[ab * PL + so] = mul_i(k1 * w0);
+            sm[(ab + 1) * PL + so] = mul_i(k2 * w0);
+            sm[(ab + 2) * PL + so] = !PF ? ld(src, 3, i) : pre[3][i];
+          }
         }
       }
       if (PF && q + 1 < wg.qe) fetch(q + 1);
       __syncthreads();
-      planes_fft<R, N, 1, true>(sm, SPLIT ? 3 : 6, threadIdx.x);
+      planes_fft<R, N, 1, true>(sm, (SPLIT || !H5) ? 3 : 6, threadIdx.x);
 #pragma unroll
       for (int i = 0; i < KP; ++i) {
         const long r = wg.zo + RB * N * i;
@@ -1725,7 +1762,7 @@ __global__ void __launch_bounds__((Fz<R, N>::NTH)) k_fused_O(const cx<R>* buf4, 
           const cx<R> pq = psi[long(q) * NR + r];
 #pragma unroll
           for (int d = 0; d < 3; ++d) Y[d] = sm[d * PL + so];
-          h5[i] += wq * norm2(Y);
+          if constexpr (H5) h5[i] += wq * norm2(Y);
 #pragma unroll
           for (int d = 0; d < 3; ++d) {
             const cx<R> hv = cmulc(mk<R>(Y[d].x, cj ? -Y[d].y : Y[d].y), pq);   // Y conjugated when reflected
@@ -2006,11 +2043,13 @@ __global__ void k_sum_parts(int mode, int S, int T, int t0, int slot, const R* h
 #pragma unroll
       for (int s = 0; s < 3; ++s) {
         const cx<R> v = gpart[((long(c) * T + t) * 3 + s) * NR + r];
-        const cx<R> u = h4part[((long(c) * T + t) * 3 + s) * NR + r];
         g[s].x += double(v.x);
         g[s].y += double(v.y);
-        h[s].x += double(u.x);
-        h[s].y += double(u.y);
+        if (h4part) {
+          const cx<R> u = h4part[((long(c) * T + t) * 3 + s) * NR + r];
+          h[s].x += double(u.x);
+          h[s].y += double(u.y);
+        }
       }
     }
 #pragma unroll
@@ -2018,7 +2057,7 @@ __global__ void k_sum_parts(int mode, int S, int T, int t0, int slot, const R* h
       cx<double>& a = acc[(long(s) * T + t) * NR + r];
       a.x += g[s].x;
       a.y += g[s].y;
-      h4[(long(t) * 3 + s) * NR + r] = mk<R>(R(h[s].x), R(h[s].y));
+      if (h4part) h4[(long(t) * 3 + s) * NR + r] = mk<R>(R(h[s].x), R(h[s].y));
     }
   } else {
     cx<double> g = {0, 0};
@@ -2126,6 +2165,45 @@ __global__ void k_reduce_occ(const H5* h5, const cx<R>* H3c, const cx<R>* psi, c
   h6[r] = mk<R>(R(s), R(si));
 #pragma unroll
   for (int c = 0; c < 3; ++c) M[c * NR + r] = mk<R>(R(mr[c]), R(mi[c]));
+}
+
+// 3a2 with h5 from pass A (k_fused_A<H5A>), applied after every target batch: h6 = sum_a w_a h5_a (fixed-order
+// FP64 sum, as in k_reduce_occ) ...
+template <typename R, int N>
+__global__ void k_h6_sum(const R* h5, const double* w, int P, cx<R>* h6) {
+  constexpr long NR = long(N) * N * N;
+  const long r = long(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (r >= NR) return;
+  double s = 0;
+  for (int a = 0; a < P; ++a) s += w[a] * double(h5[long(a) * NR + r]);
+  h6[r] = mk<R>(R(s), R(0));
+}
+// ... then per target batch g_t = coef h6 psi_j (coef = m3a2 / 2, the local 3a2 term that k_local leaves out
+// on this path), for the r -> G transform and a gather that adds it to the output ...
+template <typename R, int N>
+__global__ void k_h6_apply(const cx<R>* psi, const cx<R>* h6, int t0, int T, R coef, cx<R>* g) {
+  constexpr long NR = long(N) * N * N;
+  const long id = long(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (id >= long(T) * NR) return;
+  const int t = int(id / NR);
+  const long r = id - long(t) * NR;
+  g[long(t) * NR + r] = (coef * h6[r]) * psi[long(t0 + t) * NR + r];
+}
+// ... and its energy, added to the three-body slot: e[j kAccSlots + slot] += Re sum_r conj(psi_j) coef h6 psi_j / N^3
+// (one work-group per target, deterministic sum)
+template <typename R, int N>
+__global__ void __launch_bounds__(256) k_h6_energy(const cx<R>* psi, const cx<R>* h6, int t0, double coef, int slot,
+                                                   double* e) {
+  constexpr long NR = long(N) * N * N;
+  const int j = t0 + int(blockIdx.x);
+  const cx<R>* p = psi + long(j) * NR;
+  double s = 0;
+  for (long r = threadIdx.x; r < NR; r += blockDim.x) {
+    const double a = double(p[r].x), b = double(p[r].y);
+    s += double(h6[r].x) * (a * a + b * b);
+  }
+  s = wg_sum(s);
+  if (threadIdx.x == 0) e[long(j) * kAccSlots + slot] += coef * s / double(NR);
 }
 
 // Pass-B target factor in lattice components: Zl_t = B (m2bx2 D_j - m3b3 h1 psi_j + m3b4 h4_t)
