@@ -1962,13 +1962,15 @@ struct EngineT : Engine {
       K(TC_K_OTHER, fb * 0.5 * P + fb, [&] {
         hipLaunchKernelGGL((k_h6_sum<R, N>), dim3(nblk(NR)), dim3(256), 0, s, H5P[0], W[0], P, h6);
       });
+      K(TC_K_OTHER, fb * (NTG + 1.0), [&] {   // one work-group per target
+        hipLaunchKernelGGL((k_h6_energy<R, N>), dim3(NTG), dim3(256), 0, s, XS[0], h6, 0, 0.5 * m.m3a2, 2,
+                           sh.epart.p);
+      });
       for (int t0 = 0; t0 < NTG; t0 += T) {
         const int nt = std::min(T, NTG - t0);
         K(TC_K_OTHER, fb * (2.0 * nt + 1.0), [&] {
           hipLaunchKernelGGL((k_h6_apply<R, N>), dim3(nblk(long(nt) * NR)), dim3(256), 0, s, PSI[0], h6, t0, nt,
                              R(0.5 * m.m3a2), g.p);
-          hipLaunchKernelGGL((k_h6_energy<R, N>), dim3(nt), dim3(256), 0, s, XS[0], h6, t0, 0.5 * m.m3a2, 2,
-                             sh.epart.p);
         });
         fft3d_t<R, N>(g.p, nt, -1, s, pf);
         K(TC_K_OTHER, 0.0, [&] {
