@@ -1657,15 +1657,19 @@ struct PassO {
 // spin and of the other spin respectively.
 // H5 = false: only H3a4, from the parallel channel's three planes (h5part is written as zeros); in TC mode
 // with the pair store, pass A accumulates h5 of every target from the same fields (k_fused_A<H5A>).
+// In FP32 at 48 points the parallel-only form (three planes, 56 KB of LDS) runs two 768-thread work-groups per
+// CU at 80 registers, without the register prefetch (measured faster than one work-group with it).
+template <typename R, int N, bool H5>
+constexpr int kFusedOWaves = (!H5 && Fz<R, N>::TWO_WG) ? 6 : 1;
 template <typename R, int N, bool SPLITH = false, bool H5 = true>
-__global__ void __launch_bounds__((Fz<R, N>::NTH)) k_fused_O(const cx<R>* buf4, const cx<R>* psi, const double* w,
-                                                           FusedArgs fa, MeshInfo mi, Recip rc, const double* dfr,
-                                                           R* h5part, cx<R>* H3part, long sT = -1, long sQ = 4,
-                                                           const cx<R>* trs = nullptr, int Q1 = 0) {
+__global__ void __launch_bounds__((Fz<R, N>::NTH)) __attribute__((amdgpu_waves_per_eu(kFusedOWaves<R, N, H5>)))
+k_fused_O(const cx<R>* buf4, const cx<R>* psi, const double* w, FusedArgs fa, MeshInfo mi, Recip rc,
+          const double* dfr, R* h5part, cx<R>* H3part, long sT = -1, long sQ = 4, const cx<R>* trs = nullptr,
+          int Q1 = 0) {
   using F = Fz<R, N>;
   constexpr int KP = F::KP, RB = F::RB, PL = F::PLANE;
   constexpr bool SPLIT = H5 && PassO<R, N>::SPLIT;
-  constexpr bool PF = !SPLIT && F::PREFETCH;
+  constexpr bool PF = !SPLIT && F::PREFETCH && (H5 || !F::TWO_WG);
   constexpr int NF = H5 ? 4 : 2;   // pair fields read: W0, W3 of the parallel channel (and the antiparallel)
   if (sT < 0) sT = 4L * fa.P;
   constexpr long NR = long(N) * N * N;
@@ -1707,7 +1711,9 @@ __global__ void __launch_bounds__((Fz<R, N>::NTH)) k_fused_O(const cx<R>* buf4, 
     }
     return buf4 + (long(wg.t) * sT + long(q) * sQ) * NR;
   };
-  auto ld = [&](const cx<R>* src, int f, int i) -> cx<R> { return src[f * NR + wg.zo + RB * N * i]; };
+  auto ld = [&](const cx<R>* src, int f, int i) -> cx<R> {
+    return ldo(uniform_global(src) + f * NR, (wg.zo + RB * N * i) * unsigned(sizeof(cx<R>)));
+  };
   // the next partner's four pair planes are loaded into registers while this partner is transformed
   cx<R> pre[NF][KP];
   auto fetch = [&](int q) {
@@ -1759,7 +1765,7 @@ __global__ void __launch_bounds__((Fz<R, N>::NTH)) k_fused_O(const cx<R>* buf4, 
         const int so = wg.ss(i);
         cx<R> Y[3];
         if (par) {
-          const cx<R> pq = psi[long(q) * NR + r];
+          const cx<R> pq = ldo(uniform_global(psi + long(q) * NR), unsigned(r) * unsigned(sizeof(cx<R>)));
 #pragma unroll
           for (int d = 0; d < 3; ++d) Y[d] = sm[d * PL + so];
           if constexpr (H5) h5[i] += wq * norm2(Y);
