@@ -492,12 +492,14 @@ __device__ __forceinline__ void comb16(cx<R>* line) {
 // The combs of np planes' lines along one axis, one (line, comb) per task: every thread of the
 // work-group takes part.  The comb index is uniform over most waves; it selects one of three
 // compile-time address patterns.
-template <typename R, int DIR, bool COL>
+template <typename R, int DIR, bool COL, bool FENCE = false>
 __device__ __forceinline__ void comb_pass48(cx<R>* sm, int np, int tid, int nth) {
   constexpr int N = 48, LD = N + 1, PL = N * LD;
   const int nl = np * N;
   for (int t = tid; t < 3 * nl; t += nth) {
-    const int n1 = t / nl, r = t - n1 * nl;
+    int tt = t;   // FENCE: recomputed per pass, not held across the caller's loop (compiler-only fence)
+    if constexpr (FENCE) asm volatile("" : "+v"(tt));
+    const int n1 = tt / nl, r = tt - n1 * nl;
     const int p = r / N, l = r - p * N;
     cx<R>* line = COL ? sm + p * PL + l : sm + p * PL + l * LD;
     if (n1 == 0)
@@ -524,12 +526,14 @@ __device__ __forceinline__ void comb_pass48(cx<R>* sm, int np, int tid, int nth)
 // a thread a whole row's three combs in turn (fewer threads busy, a shorter instruction stream) and the
 // column pass takes one (column, comb) per task, which measured faster in k_fused_A's inverse transforms
 // and slower everywhere else (k_fused_A's forward transforms, k_fused_O, k_passB_xy, k_fused_Y, k_pair_xy).
-template <typename R, int DIR, bool BAL>
+// FENCE: the task addresses are recomputed in each call rather than kept in registers across the caller's
+// loop (for a kernel whose registers are short).
+template <typename R, int DIR, bool BAL, bool FENCE = false>
 __device__ __forceinline__ void planes_comb48(cx<R>* sm, int np, int tid, int nth) {
   constexpr int N = 48, LD = N + 1, PL = N * LD;
   if constexpr (BAL) {
-    comb_pass48<R, DIR, false>(sm, np, tid, nth);
-    comb_pass48<R, DIR, true>(sm, np, tid, nth);
+    comb_pass48<R, DIR, false, FENCE>(sm, np, tid, nth);
+    comb_pass48<R, DIR, true, FENCE>(sm, np, tid, nth);
   } else {
     for (int t = tid; t < np * N; t += nth) {
       const int p = t / N, y = t - p * N;
@@ -541,10 +545,12 @@ __device__ __forceinline__ void planes_comb48(cx<R>* sm, int np, int tid, int nt
       comb16<R, DIR, 2, 1>(row);
     }
     __syncthreads();
-    comb_pass48<R, DIR, true>(sm, np, tid, nth);
+    comb_pass48<R, DIR, true, FENCE>(sm, np, tid, nth);
   }
   for (int t = tid; t < np * 256; t += nth) {
-    const int p = t >> 8, ky = (t >> 4) & 15, kx = t & 15;
+    int tt = t;
+    if constexpr (FENCE) asm volatile("" : "+v"(tt));
+    const int p = tt >> 8, ky = (tt >> 4) & 15, kx = tt & 15;
     cx<R>* pl = sm + p * PL;
     int xo[3], yo[3];
 #pragma unroll
@@ -581,10 +587,10 @@ __device__ __forceinline__ void planes_comb48(cx<R>* sm, int np, int tid, int nt
 // round's writes need no barrier between them: only the barrier before the next transform.  At N = 48
 // the transform is planes_comb48: reads after it use PlaneWG::ss (sigma order), and a barrier separates
 // them from the next round's writes (end_round).
-template <typename R, int N, int DIR, bool BAL = false>
+template <typename R, int N, int DIR, bool BAL = false, bool FENCE = false>
 __device__ __forceinline__ void planes_fft(cx<R>* sm, int np, int tid) {
   if constexpr (Fz<R, N>::COMB) {
-    planes_comb48<R, DIR, BAL>(sm, np, tid, Fz<R, N>::NTH);
+    planes_comb48<R, DIR, BAL, FENCE>(sm, np, tid, Fz<R, N>::NTH);
     return;
   }
   constexpr int LD = N + 1, RB = Fz<R, N>::RB;
@@ -1732,7 +1738,11 @@ k_fused_O(const cx<R>* buf4, const cx<R>* psi, const double* w, FusedArgs fa, Me
     bool cj;
     const cx<R>* src = pairsrc(q, cj);
     const double dsg = cj ? -1.0 : 1.0;   // shift of the loaded pair relative to (q, ja)
-    const R k1 = R(double(mfreq<N>(wg.x)) + dsg * del[0]);
+    // grid frequencies (exact in R) recomputed per partner rather than held across the loop (compiler-only
+    // fences); the shift rounded once to R
+    int xx = wg.x, yy = wg.y0;
+    asm volatile("" : "+v"(xx), "+v"(yy));
+    const R k1 = R(mfreq<N>(xx)) + R(dsg * del[0]);
 #pragma unroll 1
     for (int g = 0; g < (SPLIT ? 2 : 1); ++g) {
       const bool par = !SPLIT || g == 0, anti = H5 && (!SPLIT || g == 1);
@@ -1740,7 +1750,7 @@ k_fused_O(const cx<R>* buf4, const cx<R>* psi, const double* w, FusedArgs fa, Me
 #pragma unroll
       for (int i = 0; i < KP; ++i) {
         const int so = wg.so0 + RB * F::LD * i;
-        const R k2 = R(double(mfreq<N>(wg.y0 + RB * i)) + dsg * del[1]);
+        const R k2 = R(mfreq<N>(yy + RB * i)) + R(dsg * del[1]);
         if (par) {
           const cx<R> w0 = !PF ? ld(src, 0, i) : pre[0][i];
           sm[so] = mul_i(k1 * w0);
@@ -1758,7 +1768,7 @@ k_fused_O(const cx<R>* buf4, const cx<R>* psi, const double* w, FusedArgs fa, Me
       }
       if (PF && q + 1 < wg.qe) fetch(q + 1);
       __syncthreads();
-      planes_fft<R, N, 1, true>(sm, (SPLIT || !H5) ? 3 : 6, threadIdx.x);
+      planes_fft<R, N, 1, true, kFusedOWaves<R, N, H5> != 1>(sm, (SPLIT || !H5) ? 3 : 6, threadIdx.x);
 #pragma unroll
       for (int i = 0; i < KP; ++i) {
         const long r = wg.zo + RB * N * i;
