@@ -1404,11 +1404,11 @@ struct EngineT : Engine {
     const int Q1 = (!ts && !sym && need_occ && need_A) ? pair_store(pb) : 0;   // stored partner columns
     const bool keepA = Q1 > 0;
     const bool tri = keepA && !pb.bitc;   // TC mode: the triangular store (tri_row)
-    // TC mode, one channel, with the store: h5 of Alg. 3a2 comes from pass A (k_fused_A<H5A>), whose targets are
+    // TC mode with the store (one or two channels): h5 of Alg. 3a2 comes from pass A (k_fused_A<H5A>), whose targets are
     // the occupied pass's rows and whose pair fields are the conjugates of the occupied pass's, so the occupied
     // pass transforms the parallel channel only (H3a4).  h6 is then complete after the last target batch, and
     // its local term is applied to every target after the batches (k_h6_sum, k_h6_apply, k_h6_energy).
-    const bool h5A = tri && !pol && m.m3a2 != 0;
+    const bool h5A = tri && m.m3a2 != 0;
     ensure(pb, pair_budget(pb));
     // targets: the orbitals, or nbt trial vectors per k-point
     const int nbt = ts ? ts->nvec : nb;
@@ -1710,7 +1710,10 @@ struct EngineT : Engine {
               });
             }
             K(TC_K_FUSED_O, fb * ((h5A ? 2.0 : 4.0) * npair + P) + (pol ? 4.5 : 3.5) * fb * nt * S, [&] {
-              if (pol)
+              if (pol && h5A)
+                hipLaunchKernelGGL((k_fused_O<R, N, true, false>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, b4,
+                                   PSI[c], W[c], fa, mi, rc, dfr.p, h5part.p, H3part.p, sT, sQ, trs, Q1);
+              else if (pol)
                 hipLaunchKernelGGL((k_fused_O<R, N, true>), dim3(unsigned(nt) * N * S), dim3(NTH), 0, s, b4, PSI[c],
                                    W[c], fa, mi, rc, dfr.p, h5part.p, H3part.p, sT, sQ, trs, Q1);
               else if (h5A)
@@ -1861,6 +1864,10 @@ struct EngineT : Engine {
             if (pol && bitc)
               hipLaunchKernelGGL((k_fused_A<R, N, true, true>), g, b, 0, s, bufB.p, PSI[c], DL[c], HL[c], NJ[c], W[c], fa,
                                  m, do3b6, miT, bm, mm, dfr.p, bufA.p, gpart.p, h4part.p, nA, stp, Q1, int(tri), int(formA));
+            else if (pol && h5A)
+              hipLaunchKernelGGL((k_fused_A<R, N, true, false, true>), g, b, 0, s, bufB.p, PSI[c], DL[c], HL[c], NJ[c],
+                                 W[c], fa, m, do3b6, miT, bm, mm, dfr.p, bufA.p, gpart.p, h4part.p, nA, stp, Q1, int(tri),
+                                 int(formA), h5part.p);
             else if (pol)
               hipLaunchKernelGGL((k_fused_A<R, N, true, false>), g, b, 0, s, bufB.p, PSI[c], DL[c], HL[c], NJ[c], W[c], fa,
                                  m, do3b6, miT, bm, mm, dfr.p, bufA.p, gpart.p, h4part.p, nA, stp, Q1, int(tri), int(formA));
@@ -1875,10 +1882,13 @@ struct EngineT : Engine {
               hipLaunchKernelGGL((k_fused_A<R, N, false, false>), g, b, 0, s, bufB.p, PSI[c], DL[c], HL[c], NJ[c], W[c],
                                  fa, m, do3b6, miT, bm, mm, dfr.p, bufA.p, gpart.p, h4part.p, nA, stp, Q1, int(tri), int(formA));
           });
-          if (h5A)
-            K(TC_K_SUM_PARTS, 0.5 * fb * nt * (S + 1), [&] {
+          if (h5A)   // h5 (with two channels its parallel part; the antiparallel part in the second half)
+            K(TC_K_SUM_PARTS, (pol ? 1.0 : 0.5) * fb * nt * (S + 1), [&] {
               hipLaunchKernelGGL((k_sum_real_parts<R, N>), dim3(nblk(long(nt) * NR)), dim3(256), 0, s, S, nt, t0,
                                  h5part.p, H5P[c]);
+              if (pol)
+                hipLaunchKernelGGL((k_sum_real_parts<R, N>), dim3(nblk(long(nt) * NR)), dim3(256), 0, s, S, nt, t0,
+                                   h5part.p + size_t(S) * nt * NR, H5A[c]);
             });
           K(TC_K_SUM_PARTS, 6.0 * part + 6.0 * fd * nt + 3.0 * fb * nt, [&] {
             hipLaunchKernelGGL((k_sum_parts<R, N>), dim3(nblk(long(nt) * NR)), dim3(256), 0, s, 1, S, nt, t0, 0,
@@ -1958,25 +1968,33 @@ struct EngineT : Engine {
       }
     }
     if (h5A) {   // the local 3a2 term with h6 from pass A: h6 psi_j, r -> G, added to each target's output
-      cx<R>* h6 = LOC[0] + 6 * NR;
-      K(TC_K_OTHER, fb * 0.5 * P + fb, [&] {
-        hipLaunchKernelGGL((k_h6_sum<R, N>), dim3(nblk(NR)), dim3(256), 0, s, H5P[0], W[0], P, h6);
-      });
-      K(TC_K_OTHER, fb * (NTG + 1.0), [&] {   // one work-group per target
-        hipLaunchKernelGGL((k_h6_energy<R, N>), dim3(NTG), dim3(256), 0, s, XS[0], h6, 0, 0.5 * m.m3a2, 2,
-                           sh.epart.p);
-      });
-      for (int t0 = 0; t0 < NTG; t0 += T) {
-        const int nt = std::min(T, NTG - t0);
-        K(TC_K_OTHER, fb * (2.0 * nt + 1.0), [&] {
-          hipLaunchKernelGGL((k_h6_apply<R, N>), dim3(nblk(long(nt) * NR)), dim3(256), 0, s, PSI[0], h6, t0, nt,
-                             R(0.5 * m.m3a2), g.p);
+      for (int sp = 0; sp < ns; ++sp) {
+        // h6 of spin sp: its own rows' h5 (with two channels the parallel part, and the other spin's rows'
+        // antiparallel part)
+        cx<R>* h6 = LOC[sp] + 6 * NR;
+        const int o = 1 - sp;
+        K(TC_K_OTHER, fb * (pol ? 1.0 : 0.5) * P + fb, [&] {
+          if (pol)
+            hipLaunchKernelGGL((k_h6_pol<R, N>), dim3(nblk(NR)), dim3(256), 0, s, H5P[sp], W[sp], H5A[o], W[o], P, h6);
+          else
+            hipLaunchKernelGGL((k_h6_sum<R, N>), dim3(nblk(NR)), dim3(256), 0, s, H5P[0], W[0], P, h6);
         });
-        fft3d_t<R, N>(g.p, nt, -1, s, pf);
-        K(TC_K_OTHER, 0.0, [&] {
-          hipLaunchKernelGGL((k_gather<R>), dim3(nblk(long(nt) * tnpm)), dim3(256), 0, s, g.p, tbox, tnpw, nbt, tnpm,
-                             t0, nt, 1.0 / double(NR), sh.out.p, NR, nullptr, 1);
+        K(TC_K_OTHER, fb * (NTG + 1.0), [&] {   // one work-group per target
+          hipLaunchKernelGGL((k_h6_energy<R, N>), dim3(NTG), dim3(256), 0, s, XS[sp], h6, 0, 0.5 * m.m3a2, 2,
+                             sh.epart.p + size_t(kAccSlots) * sp * P);
         });
+        for (int t0 = 0; t0 < NTG; t0 += T) {
+          const int nt = std::min(T, NTG - t0);
+          K(TC_K_OTHER, fb * (2.0 * nt + 1.0), [&] {
+            hipLaunchKernelGGL((k_h6_apply<R, N>), dim3(nblk(long(nt) * NR)), dim3(256), 0, s, PSI[sp], h6, t0, nt,
+                               R(0.5 * m.m3a2), g.p);
+          });
+          fft3d_t<R, N>(g.p, nt, -1, s, pf);
+          K(TC_K_OTHER, 0.0, [&] {
+            hipLaunchKernelGGL((k_gather<R>), dim3(nblk(long(nt) * tnpm)), dim3(256), 0, s, g.p, tbox, tnpw, nbt, tnpm,
+                               t0, nt, 1.0 / double(NR), sh.out.p + sp * cofs, NR, nullptr, 1);
+          });
+        }
       }
     }
     if (ts && ts->OBh4) band_grid(s, sh, pb, *ts, NTG, psiT.p, tbox, tnpw, tkg, tnpm, rc);

@@ -1390,6 +1390,7 @@ constexpr int kFusedAWaves = (sizeof(R) == 4 && N == 24) ? 3 : 1;
 // h5part ([S][T][N^3], real) in place of h4.  The occupied pass's V of the pair (a = t, b = q) is the conjugate
 // of this pair's real-space fields (its density is the conjugate, its shift the negative), so the norms are
 // the same, and its H3a4[t] = sum_q w_q conj(V_par) psi_q equals h4[t], which the caller takes from there.
+// With POL the parallel and antiparallel parts of h5 are kept apart ([2][S][T][N^3]), as in k_fused_O.
 template <typename R, int N, bool POL = false, bool CN = true, bool H5A = false>
 __global__ void __launch_bounds__((Fz<R, N>::NTH)) __attribute__((amdgpu_waves_per_eu(kFusedAWaves<R, N>)))
 k_fused_A(const cx<R>* buf5, const cx<R>* psi, const cx<R>* Dl, const cx<R>* Hl, const cx<R>* n, const double* w,
@@ -1405,7 +1406,7 @@ k_fused_A(const cx<R>* buf5, const cx<R>* psi, const cx<R>* Dl, const cx<R>* Hl,
   const PlaneWG<R, N> wg(fa);
   const int jt = fa.t0 + wg.t;
   cx<R> ga[KP][3], h4[KP][3], nk[KP], na[POL ? KP : 1];
-  R h5k[H5A ? KP : 1];
+  R h5k[H5A ? KP : 1], h5ka[(H5A && POL) ? KP : 1];
   // |X|^2 of a Cartesian vector from its lattice components Y: Y^H M Y with the metric M = B B^T
   auto norm2 = [&](const cx<R>* Y) {
     R v = M.b[0] * (Y[0].x * Y[0].x + Y[0].y * Y[0].y) + M.b[4] * (Y[1].x * Y[1].x + Y[1].y * Y[1].y) +
@@ -1422,6 +1423,7 @@ k_fused_A(const cx<R>* buf5, const cx<R>* psi, const cx<R>* Dl, const cx<R>* Hl,
 #pragma unroll
     for (int s = 0; s < 3; ++s) ga[i][s] = h4[i][s] = mk<R>(R(0), R(0));
     if constexpr (H5A) h5k[i] = R(0);
+    if constexpr (H5A && POL) h5ka[i] = R(0);
     nk[i] = ldo(n, ob[i]);
     if constexpr (POL) na[i] = ldo(nA, ob[i]);
   }
@@ -1552,7 +1554,10 @@ k_fused_A(const cx<R>* buf5, const cx<R>* psi, const cx<R>* Dl, const cx<R>* Hl,
           cx<R> y[3];
 #pragma unroll
           for (int d = 0; d < 3; ++d) y[d] = rd((ab + d) * PL + so);
-          if constexpr (H5A) h5k[i] += wq * norm2(y);
+          if constexpr (H5A && POL)
+            h5ka[i] += wq * norm2(y);
+          else if constexpr (H5A)
+            h5k[i] += wq * norm2(y);
           if (do3b6) {
 #pragma unroll
             for (int d = 0; d < 3; ++d) sm[(ab + d) * PL + so] = CN ? y[d] * nanti : nanti.x * y[d];
@@ -1572,6 +1577,8 @@ k_fused_A(const cx<R>* buf5, const cx<R>* psi, const cx<R>* Dl, const cx<R>* Hl,
         }
 #pragma unroll
       for (int i = 0; i < (H5A ? KP : 0); ++i) asm volatile("" : "+v"(h5k[i]));
+#pragma unroll
+      for (int i = 0; i < ((H5A && POL) ? KP : 0); ++i) asm volatile("" : "+v"(h5ka[i]));
       __syncthreads();
       if (do3b6) {
         // forward xy of the T planes (slots 1..6 unsplit; 1..3 or 0..2 split), then the split form
@@ -1609,6 +1616,8 @@ k_fused_A(const cx<R>* buf5, const cx<R>* psi, const cx<R>* Dl, const cx<R>* Hl,
       if constexpr (!H5A) sto(hp + s * NR, ob[i], hc[s]);
     }
     if constexpr (H5A) sto(h5part + (long(wg.c) * fa.T + wg.t) * NR, ob[i] / unsigned(sizeof(cx<R>) / sizeof(R)), h5k[i]);
+    if constexpr (H5A && POL)
+      sto(h5part + (long(fa.S + wg.c) * fa.T + wg.t) * NR, ob[i] / unsigned(sizeof(cx<R>) / sizeof(R)), h5ka[i]);
   }
 }
 
